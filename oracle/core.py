@@ -1,0 +1,144 @@
+"""Python front of the C oracle (test infrastructure only).
+
+``normalise`` applies the definitions of Section 3 to a raw hyperedge list:
+a hypergraph's hyperedges form a *set* (duplicates collapse, first occurrence
+kept), the empty set and singletons are ignored by fill-in (Section 4.3), and
+a hyperedge is a set of nodes (a repeated node is an input error).  The
+per-size lists keep first-occurrence order, which is the stratum order the
+sampler indexes (Section 5, Algorithm 4).
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import build as _build
+from .classes import table
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        _lib = ctypes.CDLL(_build.ensure_built())
+        u32p = np.ctypeslib.ndpointer(dtype=np.uint32, flags="C_CONTIGUOUS")
+        i64p = np.ctypeslib.ndpointer(dtype=np.int64, flags="C_CONTIGUOUS")
+        i64 = ctypes.c_int64
+        _lib.oracle_count_exact.argtypes = [ctypes.c_int, ctypes.c_uint32, u32p, i64, u32p, i64, u32p, i64, i64p]
+        _lib.oracle_count_exact.restype = ctypes.c_int
+        _lib.oracle_sampled_raw.argtypes = [ctypes.c_int, ctypes.c_uint32, u32p, i64, u32p, i64, u32p, i64,
+                                            i64p, i64, i64p, i64, i64p, i64, i64p]
+        _lib.oracle_sampled_raw.restype = ctypes.c_int
+        _lib.oracle_class_canon.argtypes = [ctypes.c_int, u32p]
+        _lib.oracle_class_canon.restype = ctypes.c_int
+        _lib.oracle_pattern_class.argtypes = [ctypes.c_int, ctypes.c_uint32]
+        _lib.oracle_pattern_class.restype = ctypes.c_int
+    return _lib
+
+
+class InputError(ValueError):
+    pass
+
+
+@dataclass
+class Normalised:
+    n_nodes: int
+    by_size: dict            # size j -> int64 array (n_j, j), ascending rows, first-occurrence order
+    n_dropped_singletons: int
+    n_duplicates: int
+    order: list              # every unique hyperedge (ascending tuple), first-occurrence order
+
+    def edges(self, j: int) -> np.ndarray:
+        return self.by_size.get(j, np.zeros((0, j), dtype=np.int64))
+
+    def count(self, j: int) -> int:
+        return len(self.edges(j))
+
+
+def normalise(h) -> Normalised:
+    """Set semantics of Section 3 applied to a ``workloads.Hypergraph``."""
+    off = h.offsets.astype(np.int64)
+    mem = h.members.astype(np.int64)
+    seen = {}
+    lists = {}
+    order = []
+    singles = dups = 0
+    for i in range(len(off) - 1):
+        e = mem[off[i]:off[i + 1]].tolist()
+        if len(e) == 0:
+            raise InputError(f"hyperedge {i} is empty")
+        if any(v < 0 or v >= h.n_nodes for v in e):
+            raise InputError(f"hyperedge {i} has a node id outside [0, {h.n_nodes})")
+        if len(set(e)) != len(e):
+            raise InputError(f"hyperedge {i} repeats a node")
+        if len(e) == 1:
+            singles += 1
+            continue
+        key = tuple(sorted(e))
+        if key in seen:
+            dups += 1
+            continue
+        seen[key] = i
+        order.append(key)
+        lists.setdefault(len(key), []).append(key)
+    by_size = {j: np.array(v, dtype=np.int64).reshape(-1, j) for j, v in lists.items()}
+    return Normalised(h.n_nodes, by_size, singles, dups, order)
+
+
+def _flat(nh: Normalised, j: int) -> np.ndarray:
+    return np.ascontiguousarray(nh.edges(j).reshape(-1), dtype=np.uint32)
+
+
+def count_exact(h, k: int) -> np.ndarray:
+    """Exact counts per class (Algorithm 2 for k=3, Algorithm 3 for k=4)."""
+    nh = h if isinstance(h, Normalised) else normalise(h)
+    out = np.zeros(table(k).n_classes, dtype=np.int64)
+    rc = lib().oracle_count_exact(k, nh.n_nodes, _flat(nh, 2), nh.count(2), _flat(nh, 3), nh.count(3),
+                                  _flat(nh, 4), nh.count(4), out)
+    if rc != 0:
+        raise RuntimeError("oracle_count_exact failed")
+    return out
+
+
+def sampled_raw(h, k: int, samples: dict) -> np.ndarray:
+    """Raw per-class counts of Algorithm 4 for explicit sample lists.
+
+    ``samples[j]`` lists indices into the size-j hyperedges (first-occurrence
+    order), with repetition for draws with replacement.
+    """
+    nh = h if isinstance(h, Normalised) else normalise(h)
+    s = {j: np.ascontiguousarray(np.asarray(samples.get(j, []), dtype=np.int64)) for j in (2, 3, 4)}
+    out = np.zeros(table(k).n_classes, dtype=np.int64)
+    rc = lib().oracle_sampled_raw(k, nh.n_nodes, _flat(nh, 2), nh.count(2), _flat(nh, 3), nh.count(3),
+                                  _flat(nh, 4), nh.count(4), s[2], len(s[2]), s[3], len(s[3]),
+                                  s[4], len(s[4]), out)
+    if rc != 0:
+        raise RuntimeError("oracle_sampled_raw failed")
+    return out
+
+
+def scale_estimate(raw: np.ndarray, k: int, n_by_size: dict, s_by_size: dict) -> np.ndarray:
+    """Correction of Algorithm 4: c * |E_maxcard| / (S_maxcard * countmax), in float64.
+
+    A class whose stratum was not sampled (S_j = 0) is reported as 0.
+    """
+    t = table(k)
+    est = np.zeros(t.n_classes, dtype=np.float64)
+    for m in range(t.n_classes):
+        j = t.maxcard[m]
+        if s_by_size.get(j, 0) > 0:
+            est[m] = float(raw[m]) * float(n_by_size.get(j, 0)) / (float(s_by_size[j]) * t.countmax[m])
+    return est
+
+
+def class_canon_c(k: int) -> list:
+    buf = np.zeros(256, dtype=np.uint32)
+    n = lib().oracle_class_canon(k, buf)
+    return buf[:n].tolist()
+
+
+def pattern_class_c(k: int, pattern: int) -> int:
+    return lib().oracle_pattern_class(k, pattern)

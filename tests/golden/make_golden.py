@@ -1,0 +1,44 @@
+"""Write the stored expected counts under tests/golden/ by running the oracle.
+
+Only ``oracle/`` and the seeded generators in ``workloads`` are called.
+Run from the repository root:  python tests/golden/make_golden.py
+"""
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+sys.path.insert(0, ROOT)
+
+import workloads as W  # noqa: E402
+from oracle import core, nulls  # noqa: E402
+
+OUT = os.path.join(ROOT, "tests", "golden", "workload_counts.json")
+
+
+def main():
+    out = {"generator": "workloads.synth, numpy PCG64", "oracle": "oracle.core.count_exact (Algorithms 2 and 3)",
+           "cases": []}
+    for name, fn, k in [("facetoface_N200_E2000", W.cfg0_facetoface_k3, 3),
+                        ("facetoface_N400_E30000", W.cfg1_facetoface_k4, 4)]:
+        h = fn(0)
+        t0 = time.time()
+        c = core.count_exact(h, k)
+        out["cases"].append({"workload": name, "seed": 0, "k": k, "counts": c.tolist(),
+                             "oracle_seconds": round(time.time() - t0, 2)})
+        print(name, k, int(c.sum()), f"{time.time() - t0:.1f}s", flush=True)
+    # null copies of the order-4 workload (stub matching, seed 1): a few copies
+    h = W.cfg1_facetoface_k4(0)
+    for copy in (0, 1, 63):
+        m, o = nulls.stub_matching(h, seed=1, copy=copy)
+        c = core.count_exact(W.Hypergraph(h.n_nodes, m, o), 4)
+        out["cases"].append({"workload": "facetoface_N400_E30000/null", "seed": 0, "null_seed": 1,
+                             "copy": copy, "k": 4, "counts": c.tolist()})
+        print("null copy", copy, int(c.sum()), flush=True)
+    with open(OUT, "w") as f:
+        json.dump(out, f, indent=1)
+
+
+if __name__ == "__main__":
+    main()
