@@ -1,0 +1,124 @@
+/*
+ * homotif.h -- C ABI of the homotif library: exact and hyperedge-sampled
+ * counting of higher-order motifs of order 3 and 4 on AMD MI355X (gfx950).
+ *
+ * Paper: Lotito, Musciotto, Battiston, Montresor, "Exact and sampling methods
+ * for mining higher-order motifs in large hypergraphs" (arXiv 2209.10241).
+ *
+ * Problem (Section 3, "Mining higher-order motifs"): given a hypergraph
+ * H = (V, E) and an order k, count, for every isomorphism class of connected
+ * k-node sub-hypergraphs, how many node sets V' (|V'| = k) induce a
+ * sub-hypergraph H[V'] = (V', {e in E : e subset of V'}) of that class.
+ *
+ * Conventions shared by every entry point
+ *   - Node ids are uint32 in [0, n_nodes).  A hypergraph is given in CSR form:
+ *     hyperedge i is members[offsets[i] .. offsets[i+1]), offsets[0] = 0.
+ *   - Hyperedges form a set (Section 3): repeated hyperedges collapse, the
+ *     first occurrence is kept.  Singletons are dropped (the fill-in step of
+ *     Section 4.3 ignores them).  Hyperedges with more than k nodes cannot lie
+ *     inside a k-node set and do not affect counts.
+ *   - Stratum order: the unique hyperedges of size j, in order of first
+ *     occurrence in the input, are indexed 0 .. |E_j|-1 (Algorithm 4 samples
+ *     these strata).
+ *   - Class numbering: the k nodes of a set take local positions 0..k-1 in
+ *     ascending id order; pattern bit i marks the i-th subset of size >= 2 of
+ *     {0..k-1} in ascending mask order (k=4: masks 3,5,6,7,9,10,11,12,13,14,15;
+ *     k=3: 3,5,6,7) as a hyperedge; the canonical pattern of a class is the
+ *     smallest pattern value over all k! relabellings; class ids rank the
+ *     canonical patterns of connected classes ascending.  There are 6 classes
+ *     for k=3 and 171 for k=4 (hm_num_classes, hm_class_info).
+ *   - Ownership: the caller owns every buffer it passes.  Output pointers of
+ *     the count_* calls are DEVICE pointers; the work is enqueued on `stream`
+ *     (a hipStream_t, NULL for the default stream) and the outputs are valid
+ *     once that stream has synchronised.  The library never keeps caller
+ *     pointers after a call returns.  A graph handle owns its device memory
+ *     until hm_graph_destroy.  Calls that use one graph handle must be
+ *     serialised (one stream at a time): the handle holds reusable scratch.
+ *   - Errors: every entry point returns HM_OK (0) or a negative HM_E* code and
+ *     never aborts; on error outputs are left unspecified and hm_last_error()
+ *     returns a message (thread-local).
+ */
+#ifndef HOMOTIF_H
+#define HOMOTIF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HM_OK 0
+#define HM_EINVAL (-1)        /* bad argument or malformed input */
+#define HM_EUNSUPPORTED (-2)  /* valid request the library does not implement */
+#define HM_ENOMEM (-3)        /* device allocation failed */
+#define HM_EDEVICE (-4)       /* HIP runtime error */
+#define HM_EINTERNAL (-5)     /* internal consistency check failed */
+
+#define HM_MEM_HOST 0
+#define HM_MEM_DEVICE 1
+
+typedef struct hm_graph hm_graph;
+
+/* Message describing the last error on this thread ("" if none). */
+const char* hm_last_error(void);
+
+/* Library version string. */
+const char* hm_version(void);
+
+/* ---------------------------------------------------------------- classes */
+
+/* Number of isomorphism classes of connected k-node patterns: 6 for k=3,
+ * 171 for k=4 (Section 4.3 builds them by relabelling every pattern);
+ * HM_EUNSUPPORTED for other k. */
+int hm_num_classes(int k);
+
+/* Canonical pattern, maxcard (size of the largest hyperedge) and countmax
+ * (number of hyperedges of that size) of class `cls` of order k; the last two
+ * are the quantities of the correction factor of Algorithm 4.  Any output
+ * pointer may be NULL.  Host pointers. */
+int hm_class_info(int k, int cls, uint32_t* canon_pattern, int* maxcard, int* countmax);
+
+/* Class id of a labelled pattern (encoding above) into *cls (host pointer),
+ * -1 when the pattern is not connected; HM_EINVAL for a pattern out of
+ * range. */
+int hm_pattern_class(int k, uint32_t pattern, int* cls);
+
+/* ---------------------------------------------------------------- graphs */
+
+/* Build the device-resident hypergraph (Definition of a hypergraph,
+ * Section 3): validate, sort members, collapse repeated hyperedges, split by
+ * size, hash every hyperedge of size 2..4 (Section 4.3, Fig. 3b) and build the
+ * adjacency used by the enumeration.
+ *   members  n_members = offsets[n_edges] node ids; offsets n_edges+1 values
+ *   mem_kind HM_MEM_HOST or HM_MEM_DEVICE: where members and offsets live
+ *   stream   hipStream_t for the build (the call synchronises it before return)
+ *   out      receives the handle
+ * Errors: HM_EINVAL for an empty hyperedge, a node id >= n_nodes, a node
+ * repeated inside a hyperedge, non-monotone offsets or n_nodes = 0. */
+int hm_graph_create(const uint32_t* members, const uint64_t* offsets, uint64_t n_edges,
+                    uint32_t n_nodes, int mem_kind, void* stream, hm_graph** out);
+
+/* Release a graph handle (NULL is accepted). */
+int hm_graph_destroy(hm_graph* H);
+
+/* Host array of 8 values: n_nodes, unique hyperedges of size 2, 3, 4, unique
+ * hyperedges of size >= 5, input hyperedges, dropped singletons, collapsed
+ * repeats. */
+int hm_graph_stats(const hm_graph* H, uint64_t* out8);
+
+/* Copy the unique hyperedges of size j (2..4), stratum order, as ascending
+ * j-tuples into the host buffer `out` (|E_j| * j values). */
+int hm_graph_export(const hm_graph* H, int j, uint32_t* out);
+
+/* ---------------------------------------------------------------- exact */
+
+/* Exact counts of every order-k motif (k = 3: Algorithm 2; k = 4:
+ * Algorithm 3).  counts: device int64 array of hm_num_classes(k) values,
+ * overwritten.  Asynchronous on `stream`. */
+int count_exact(const hm_graph* H, int k, int64_t* counts, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HOMOTIF_H */

@@ -1,0 +1,6 @@
+"""homotif: exact and hyperedge-sampled counting of higher-order motifs of
+order 3 and 4 on AMD MI355X, behind the C ABI of include/homotif.h."""
+from .binding import (  # noqa: F401
+    Graph, HMError, LibraryMissing, count_exact, hm_class_info, hm_graph_create, hm_num_classes,
+    hm_pattern_class, hm_version, lib,
+)

@@ -1,0 +1,198 @@
+"""Thin ctypes binding of libhomotif.so (names follow include/homotif.h).
+
+Argument marshalling only: every step of the counting runs in the HIP
+library.  Device memory and streams come from PyTorch; outputs are torch
+tensors on the current device.  Importing this module does not need a GPU;
+calling a counting entry point does.  When the library has not been built,
+every entry point raises ``LibraryMissing``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libhomotif.so")
+
+HM_OK = 0
+HM_EINVAL = -1
+HM_EUNSUPPORTED = -2
+HM_ENOMEM = -3
+HM_EDEVICE = -4
+HM_EINTERNAL = -5
+HM_MEM_HOST = 0
+HM_MEM_DEVICE = 1
+
+_ERROR_NAMES = {HM_EINVAL: "HM_EINVAL", HM_EUNSUPPORTED: "HM_EUNSUPPORTED", HM_ENOMEM: "HM_ENOMEM",
+                HM_EDEVICE: "HM_EDEVICE", HM_EINTERNAL: "HM_EINTERNAL"}
+
+
+class LibraryMissing(ImportError):
+    pass
+
+
+class HMError(RuntimeError):
+    def __init__(self, code: int, message: str):
+        super().__init__(f"{_ERROR_NAMES.get(code, code)}: {message}")
+        self.code = code
+
+
+_lib = None
+
+_vp = ctypes.c_void_p
+_u32 = ctypes.c_uint32
+_u64 = ctypes.c_uint64
+_int = ctypes.c_int
+_dbl = ctypes.c_double
+
+# name -> (restype, argtypes)
+SIGNATURES = {
+    "hm_last_error": (ctypes.c_char_p, []),
+    "hm_version": (ctypes.c_char_p, []),
+    "hm_num_classes": (_int, [_int]),
+    "hm_class_info": (_int, [_int, _int, _vp, _vp, _vp]),
+    "hm_pattern_class": (_int, [_int, _u32, _vp]),
+    "hm_graph_create": (_int, [_vp, _vp, _u64, _u32, _int, _vp, _vp]),
+    "hm_graph_destroy": (_int, [_vp]),
+    "hm_graph_stats": (_int, [_vp, _vp]),
+    "hm_graph_export": (_int, [_vp, _int, _vp]),
+    "count_exact": (_int, [_vp, _int, _vp, _vp]),
+}
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise LibraryMissing(f"{LIB_PATH} is not built (python -m paper_2209_10241_amd.build)")
+        handle = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(handle, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = handle
+    return _lib
+
+
+def _check(rc: int) -> int:
+    if rc < 0:
+        raise HMError(rc, lib().hm_last_error().decode())
+    return rc
+
+
+def _stream_ptr(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def hm_version() -> str:
+    return lib().hm_version().decode()
+
+
+def hm_num_classes(k: int) -> int:
+    return _check(lib().hm_num_classes(k))
+
+
+def hm_class_info(k: int, cls: int):
+    canon = ctypes.c_uint32()
+    mc = ctypes.c_int()
+    cm = ctypes.c_int()
+    _check(lib().hm_class_info(k, cls, ctypes.byref(canon), ctypes.byref(mc), ctypes.byref(cm)))
+    return canon.value, mc.value, cm.value
+
+
+def hm_pattern_class(k: int, pattern: int) -> int:
+    """Class id of a labelled pattern, -1 when it is not connected."""
+    cls = ctypes.c_int()
+    _check(lib().hm_pattern_class(k, pattern, ctypes.byref(cls)))
+    return cls.value
+
+
+class Graph:
+    """Owner of an ``hm_graph`` handle."""
+
+    def __init__(self, handle: int, n_nodes: int):
+        self._h = ctypes.c_void_p(handle)
+        self.n_nodes = n_nodes
+
+    @property
+    def handle(self):
+        if self._h is None or not self._h.value:
+            raise HMError(HM_EINVAL, "graph handle already destroyed")
+        return self._h
+
+    def stats(self) -> dict:
+        out = (ctypes.c_uint64 * 8)()
+        _check(lib().hm_graph_stats(self.handle, out))
+        keys = ["n_nodes", "n2", "n3", "n4", "n5plus", "n_input", "singletons", "duplicates"]
+        return dict(zip(keys, [int(x) for x in out]))
+
+    def export(self, j: int) -> np.ndarray:
+        n = self.stats()[f"n{j}"]
+        out = np.zeros(n * j, dtype=np.uint32)
+        _check(lib().hm_graph_export(self.handle, j, out.ctypes.data_as(ctypes.c_void_p)))
+        return out.reshape(n, j)
+
+    def close(self):
+        if self._h is not None and self._h.value and _lib is not None:
+            _lib.hm_graph_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+def hm_graph_create(members, offsets, n_nodes: int, stream=None) -> Graph:
+    """members/offsets: numpy arrays (host) or CUDA torch tensors (device)."""
+    out = ctypes.c_void_p()
+    try:
+        import torch
+        is_dev = isinstance(members, torch.Tensor) and members.is_cuda
+    except ImportError:
+        is_dev = False
+    if is_dev:
+        import torch
+        members = members.to(torch.int32).contiguous()
+        offsets = offsets.to(torch.int64).contiguous()
+        n_edges = offsets.numel() - 1
+        rc = lib().hm_graph_create(ctypes.c_void_p(members.data_ptr()), ctypes.c_void_p(offsets.data_ptr()),
+                                   n_edges, n_nodes, HM_MEM_DEVICE, _stream_ptr(stream), ctypes.byref(out))
+    else:
+        m = np.ascontiguousarray(members, dtype=np.uint32)
+        o = np.ascontiguousarray(offsets, dtype=np.uint64)
+        n_edges = len(o) - 1
+        st = _stream_ptr(stream) if _cuda_available() else ctypes.c_void_p(0)
+        rc = lib().hm_graph_create(m.ctypes.data_as(ctypes.c_void_p), o.ctypes.data_as(ctypes.c_void_p),
+                                   n_edges, n_nodes, HM_MEM_HOST, st, ctypes.byref(out))
+    _check(rc)
+    return Graph(out.value, n_nodes)
+
+
+def _cuda_available() -> bool:
+    try:
+        import torch
+        return torch.cuda.is_available()
+    except ImportError:
+        return False
+
+
+def count_exact(H: Graph, k: int, out=None, stream=None):
+    """Exact per-class counts (int64 torch tensor on the current device)."""
+    import torch
+    n = hm_num_classes(k)
+    if out is None:
+        out = torch.empty(n, dtype=torch.int64, device="cuda")
+    _check(lib().count_exact(H.handle, k, ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)))
+    return out

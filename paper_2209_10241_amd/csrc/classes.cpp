@@ -1,0 +1,225 @@
+// Isomorphism classes of k-node patterns and the pattern -> class lookup
+// table (Section 4.3, Fig. 3a): every labelled pattern of interactions among
+// k nodes is mapped to its class, so classifying an observed sub-hypergraph
+// is one table read.  Built once per process on the host, copied per device.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <array>
+#include <cstdarg>
+#include <cstring>
+#include <mutex>
+#include <numeric>
+#include <vector>
+
+#include "hm_internal.h"
+
+namespace hm {
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+struct Subsets {
+  std::vector<int> masks;  // subsets of {0..k-1} with >= 2 members, ascending mask
+};
+
+Subsets subsets_of(int k) {
+  Subsets s;
+  for (int m = 0; m < (1 << k); ++m)
+    if (__builtin_popcount(m) >= 2) s.masks.push_back(m);
+  return s;
+}
+
+bool connected(uint32_t pattern, int k, const Subsets& s) {
+  // grow the component of node 0 until it stops changing
+  unsigned covered = 0;
+  for (size_t b = 0; b < s.masks.size(); ++b)
+    if (pattern >> b & 1u) covered |= unsigned(s.masks[b]);
+  if (covered != (1u << k) - 1) return false;
+  unsigned comp = 1u;
+  bool grew = true;
+  while (grew) {
+    grew = false;
+    for (size_t b = 0; b < s.masks.size(); ++b) {
+      unsigned m = unsigned(s.masks[b]);
+      if ((pattern >> b & 1u) && (m & comp) && (m & ~comp)) {
+        comp |= m;
+        grew = true;
+      }
+    }
+  }
+  return comp == (1u << k) - 1;
+}
+
+uint32_t relabel(uint32_t pattern, const std::array<int, 4>& perm, int k, const Subsets& s,
+                 const std::vector<int>& index_of_mask) {
+  uint32_t out = 0;
+  for (size_t b = 0; b < s.masks.size(); ++b) {
+    if (!(pattern >> b & 1u)) continue;
+    int img = 0;
+    for (int i = 0; i < k; ++i)
+      if (s.masks[b] >> i & 1) img |= 1 << perm[i];
+    out |= 1u << index_of_mask[img];
+  }
+  return out;
+}
+
+ClassTables build() {
+  ClassTables t;
+  std::memset(&t, 0, sizeof(t));
+  for (int k = 3; k <= 4; ++k) {
+    const Subsets s = subsets_of(k);
+    std::vector<int> index_of_mask(1 << k, -1);
+    for (size_t b = 0; b < s.masks.size(); ++b) index_of_mask[s.masks[b]] = int(b);
+    const uint32_t n_patterns = 1u << s.masks.size();
+    std::vector<std::array<int, 4>> perms;
+    std::array<int, 4> p{0, 1, 2, 3};
+    do {
+      perms.push_back(p);
+    } while (std::next_permutation(p.begin(), p.begin() + k));
+    std::vector<uint32_t> canon(n_patterns, 0xFFFFFFFFu);
+    std::vector<uint32_t> classes;
+    for (uint32_t q = 0; q < n_patterns; ++q) {
+      if (!connected(q, k, s)) continue;
+      uint32_t best = 0xFFFFFFFFu;
+      for (const auto& pm : perms) best = std::min(best, relabel(q, pm, k, s, index_of_mask));
+      canon[q] = best;
+      classes.push_back(best);
+    }
+    std::sort(classes.begin(), classes.end());
+    classes.erase(std::unique(classes.begin(), classes.end()), classes.end());
+    t.n_classes[k] = int(classes.size());
+    uint8_t* lut = (k == 3) ? t.lut3 : t.lut4;
+    for (uint32_t q = 0; q < n_patterns; ++q) {
+      if (canon[q] == 0xFFFFFFFFu) {
+        lut[q] = 0xFF;
+        continue;
+      }
+      lut[q] = uint8_t(std::lower_bound(classes.begin(), classes.end(), canon[q]) - classes.begin());
+    }
+    for (size_t c = 0; c < classes.size(); ++c) {
+      t.canon[k][c] = classes[c];
+      int mc = 0, cm = 0;
+      for (size_t b = 0; b < s.masks.size(); ++b) {
+        if (!(classes[c] >> b & 1u)) continue;
+        int sz = __builtin_popcount(s.masks[b]);
+        if (sz > mc) {
+          mc = sz;
+          cm = 1;
+        } else if (sz == mc) {
+          ++cm;
+        }
+      }
+      t.maxcard[k][c] = uint8_t(mc);
+      t.countmax[k][c] = uint8_t(cm);
+    }
+  }
+  return t;
+}
+
+std::mutex g_lut_mutex;
+std::vector<uint8_t*> g_device_luts;  // per device: lut4 (2048) + lut3 (16)
+
+}  // namespace
+
+void set_error(const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+}
+
+const char* last_error() { return g_err; }
+
+const ClassTables& class_tables() {
+  static const ClassTables t = build();
+  return t;
+}
+
+int device_luts(int device, const uint8_t** lut4, const uint8_t** lut3) {
+  std::lock_guard<std::mutex> lock(g_lut_mutex);
+  if (device < 0) {
+    set_error("bad device %d", device);
+    return HM_EINVAL;
+  }
+  if (size_t(device) >= g_device_luts.size()) g_device_luts.resize(size_t(device) + 1, nullptr);
+  if (!g_device_luts[size_t(device)]) {
+    const ClassTables& t = class_tables();
+    uint8_t host[2048 + 16];
+    std::memcpy(host, t.lut4, 2048);
+    std::memcpy(host + 2048, t.lut3, 16);
+    void* p = nullptr;
+    HM_TRY(dalloc(&p, sizeof(host)));
+    HM_HIP(hipMemcpy(p, host, sizeof(host), hipMemcpyHostToDevice));
+    g_device_luts[size_t(device)] = static_cast<uint8_t*>(p);
+  }
+  *lut4 = g_device_luts[size_t(device)];
+  *lut3 = g_device_luts[size_t(device)] + 2048;
+  return HM_OK;
+}
+
+int dalloc(void** p, size_t bytes) {
+  *p = nullptr;
+  if (bytes == 0) bytes = 16;
+  hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    set_error("hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+    return e == hipErrorOutOfMemory ? HM_ENOMEM : HM_EDEVICE;
+  }
+  return HM_OK;
+}
+
+void dfree(void* p) {
+  if (p) (void)hipFree(p);
+}
+
+}  // namespace hm
+
+extern "C" {
+
+const char* hm_last_error(void) { return hm::last_error(); }
+
+const char* hm_version(void) { return "homotif 0.1 (gfx950)"; }
+
+int hm_num_classes(int k) {
+  if (k != 3 && k != 4) {
+    hm::set_error("order %d is not supported (3 or 4)", k);
+    return HM_EUNSUPPORTED;
+  }
+  return hm::class_tables().n_classes[k];
+}
+
+int hm_class_info(int k, int cls, uint32_t* canon_pattern, int* maxcard, int* countmax) {
+  int n = hm_num_classes(k);
+  if (n < 0) return n;
+  if (cls < 0 || cls >= n) {
+    hm::set_error("class %d out of range [0, %d)", cls, n);
+    return HM_EINVAL;
+  }
+  const hm::ClassTables& t = hm::class_tables();
+  if (canon_pattern) *canon_pattern = t.canon[k][cls];
+  if (maxcard) *maxcard = t.maxcard[k][cls];
+  if (countmax) *countmax = t.countmax[k][cls];
+  return HM_OK;
+}
+
+int hm_pattern_class(int k, uint32_t pattern, int* cls) {
+  int n = hm_num_classes(k);
+  if (n < 0) return n;
+  if (!cls) {
+    hm::set_error("cls is NULL");
+    return HM_EINVAL;
+  }
+  const hm::ClassTables& t = hm::class_tables();
+  if (pattern >= (k == 3 ? 16u : 2048u)) {
+    hm::set_error("pattern %u out of range for order %d", pattern, k);
+    return HM_EINVAL;
+  }
+  uint8_t c = (k == 3) ? t.lut3[pattern] : t.lut4[pattern];
+  *cls = c == 0xFF ? -1 : int(c);
+  return HM_OK;
+}
+
+}  // extern "C"

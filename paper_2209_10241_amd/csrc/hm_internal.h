@@ -1,0 +1,185 @@
+// Internal declarations of the homotif HIP library (gfx950).
+//
+// Device-resident hypergraph layout, hash sets of hyperedges (Section 4.3,
+// Fig. 3b: every hyperedge is hashed so that its existence is checked in
+// constant time), error plumbing and small wavefront helpers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+
+#include "../../include/homotif.h"
+
+namespace hm {
+
+constexpr int kWave = 64;
+constexpr uint32_t kEmpty32 = 0xFFFFFFFFu;
+constexpr unsigned long long kEmpty64 = ~0ull;
+// adjacency bit rows are kept when the node count is at most this
+constexpr uint32_t kBitsetMaxNodes = 8192;
+
+// ----------------------------------------------------------------- errors
+void set_error(const char* fmt, ...);
+const char* last_error();
+struct Status {
+  int code = HM_OK;
+};
+
+#define HM_HIP(call)                                                              \
+  do {                                                                            \
+    hipError_t _e = (call);                                                       \
+    if (_e != hipSuccess) {                                                       \
+      ::hm::set_error("%s failed: %s (%s:%d)", #call, hipGetErrorString(_e),      \
+                      __FILE__, __LINE__);                                        \
+      return HM_EDEVICE;                                                          \
+    }                                                                             \
+  } while (0)
+
+#define HM_TRY(expr)          \
+  do {                        \
+    int _rc = (expr);         \
+    if (_rc != HM_OK) return _rc; \
+  } while (0)
+
+// ----------------------------------------------------------------- hashing
+__host__ __device__ inline unsigned long long mix64(unsigned long long x) {
+  x ^= x >> 31;
+  x *= 0x7fb5d329728ea185ull;
+  x ^= x >> 27;
+  x *= 0x81dadef4bc2dd44dull;
+  x ^= x >> 33;
+  return x;
+}
+
+// Keys: a 2-node hyperedge {a<b} is (a<<32)|b; 3- and 4-node hyperedges are
+// 128-bit (hi = a<<32|b, lo = c<<32|d), with d = 0xFFFFFFFF for 3 nodes.
+__host__ __device__ inline unsigned long long key2(uint32_t a, uint32_t b) {
+  return ((unsigned long long)a << 32) | b;
+}
+struct Key128 {
+  unsigned long long hi, lo;
+};
+__host__ __device__ inline Key128 key3(uint32_t a, uint32_t b, uint32_t c) {
+  return Key128{((unsigned long long)a << 32) | b, ((unsigned long long)c << 32) | 0xFFFFFFFFull};
+}
+__host__ __device__ inline Key128 key4(uint32_t a, uint32_t b, uint32_t c, uint32_t d) {
+  return Key128{((unsigned long long)a << 32) | b, ((unsigned long long)c << 32) | d};
+}
+__host__ __device__ inline unsigned long long hash128(Key128 k) {
+  return mix64(k.hi ^ mix64(k.lo + 0x9e3779b97f4a7c15ull));
+}
+
+// Open-addressing (linear probing) set of 64-bit keys; capacity is a power
+// of two with load at most 1/2; empty slots hold kEmpty64.
+struct Set64 {
+  unsigned long long* slot = nullptr;
+  unsigned long long mask = 0;
+};
+// Same with 128-bit keys stored as (hi, lo) pairs.
+struct Set128 {
+  unsigned long long* slot = nullptr;  // 2 words per slot
+  unsigned long long mask = 0;
+};
+
+__device__ inline bool set64_has(const Set64& s, unsigned long long key) {
+  unsigned long long pos = mix64(key) & s.mask;
+  while (true) {
+    unsigned long long v = s.slot[pos];
+    if (v == key) return true;
+    if (v == kEmpty64) return false;
+    pos = (pos + 1) & s.mask;
+  }
+}
+
+__device__ inline bool set128_has(const Set128& s, Key128 key) {
+  unsigned long long pos = hash128(key) & s.mask;
+  while (true) {
+    const ulonglong2 v = *reinterpret_cast<const ulonglong2*>(s.slot + 2 * pos);
+    if (v.x == key.hi && v.y == key.lo) return true;
+    if (v.x == kEmpty64) return false;
+    pos = (pos + 1) & s.mask;
+  }
+}
+
+inline unsigned long long pow2_capacity(unsigned long long n) {
+  unsigned long long cap = 64;
+  while (cap < 2 * n + 2) cap <<= 1;
+  return cap;
+}
+
+// ----------------------------------------------------------------- class tables
+// Built once per process on the host from the definitions (see classes.cpp),
+// copied to device memory per device.
+struct ClassTables {
+  int n_classes[5];             // [3] = 6, [4] = 171
+  uint8_t lut3[16];             // pattern -> class, 0xFF = not connected
+  uint8_t lut4[2048];
+  uint32_t canon[5][256];       // canonical pattern per class
+  uint8_t maxcard[5][256];
+  uint8_t countmax[5][256];
+};
+const ClassTables& class_tables();
+// device copy of lut4 (2048 bytes) followed by lut3 (16 bytes), per device
+int device_luts(int device, const uint8_t** lut4, const uint8_t** lut3);
+
+// ----------------------------------------------------------------- primitives
+int scan_exclusive_u32(const uint32_t* in, uint32_t* out, uint64_t n, uint32_t* total_dev,
+                       hipStream_t stream);
+int scan_exclusive_u64(const unsigned long long* in, unsigned long long* out, uint64_t n,
+                       hipStream_t stream);
+// Stable LSD radix sort of (key, value) pairs on bits [0, bits) of the key.
+// Buffers are ping-ponged; the sorted result ends in keys/vals (the first pair).
+int radix_sort_pairs(unsigned long long* keys, uint32_t* vals, unsigned long long* keys_tmp,
+                     uint32_t* vals_tmp, uint64_t n, int bits, hipStream_t stream);
+int fill_u32(uint32_t* p, uint32_t value, uint64_t n, hipStream_t stream);
+int fill_u64(unsigned long long* p, unsigned long long value, uint64_t n, hipStream_t stream);
+
+// ----------------------------------------------------------------- device allocations
+int dalloc(void** p, size_t bytes);
+void dfree(void* p);
+
+}  // namespace hm
+
+// ----------------------------------------------------------------- the graph handle
+struct hm_graph {
+  int device = 0;
+  uint32_t n_nodes = 0;
+  uint64_t n_input = 0;
+  uint64_t n_by_size[6] = {0, 0, 0, 0, 0, 0};  // unique hyperedges of size 2,3,4; [5] = size >= 5
+  uint64_t n_singletons = 0;
+  uint64_t n_duplicates = 0;
+  uint64_t n_unique = 0;           // unique hyperedges of size >= 2
+  uint64_t n_unique_members = 0;   // total members of those
+
+  // unique hyperedges per size, ascending tuples, first-occurrence order
+  uint32_t* e2 = nullptr;
+  uint32_t* e3 = nullptr;
+  uint32_t* e4 = nullptr;
+  // every unique hyperedge of size >= 2 (ascending members), first-occurrence order
+  uint32_t* all_members = nullptr;
+  unsigned long long* all_off = nullptr;   // n_unique + 1
+
+  hm::Set64 hs2;
+  hm::Set128 hs3, hs4;
+
+  // pairwise graph: ascending neighbour rows
+  uint32_t* g2_off = nullptr;   // n_nodes + 1
+  uint32_t* g2_adj = nullptr;   // 2 * n2
+  uint32_t max_deg2 = 0;
+  // node -> incident 3-node hyperedges (indices into e3)
+  uint32_t* i3_off = nullptr;
+  uint32_t* i3_idx = nullptr;
+  uint32_t max_deg3 = 0;
+  // node -> incident 4-node hyperedges (indices into e4)
+  uint32_t* i4_off = nullptr;
+  uint32_t* i4_idx = nullptr;
+  // adjacency bit rows of the pairwise graph (n_nodes x words), when kept
+  uint32_t* bits = nullptr;
+  uint32_t words = 0;
+
+  // histogram scratch, reused by the counting calls (serialised per graph)
+  unsigned long long* hist = nullptr;      // 4 x 256 counters
+};
