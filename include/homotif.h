@@ -117,6 +117,34 @@ int hm_graph_export(const hm_graph* H, int j, uint32_t* out);
  * overwritten.  Asynchronous on `stream`. */
 int count_exact(const hm_graph* H, int k, int64_t* counts, void* stream);
 
+/* ---------------------------------------------------------------- options */
+
+/* Process-wide tuning options (read when a graph is created).
+ *   HM_OPT_BITSET_MAX_NODES  graphs with at most this many nodes (default and
+ *                            maximum 8192) also keep adjacency bit rows, which
+ *                            the counting kernels use for pair tests and
+ *                            neighbour intersections; 0 forces the hash-set
+ *                            probes everywhere.
+ * HM_EINVAL for an unknown option or a value out of range. */
+#define HM_OPT_BITSET_MAX_NODES 1
+int hm_set_option(int option, int64_t value);
+int hm_get_option(int option, int64_t* value);
+
+/* ---------------------------------------------------------------- timing */
+
+/* Per-kernel timing for observability.  While enabled (on != 0), the counting
+ * calls bracket each kernel launch with HIP events on the caller's stream.
+ * Process-wide; not meant for concurrent use from several threads. */
+int hm_profile_enable(int on);
+
+/* Wait for recorded events and clear the accumulated totals. */
+int hm_profile_reset(void);
+
+/* Wait for recorded events and report up to max_entries kernels: names
+ * (64 bytes each, NUL-terminated), launch counts and summed milliseconds
+ * (host arrays, any may be NULL).  Returns the number of entries written. */
+int hm_profile_read(int max_entries, char* names, uint64_t* launches, double* total_ms);
+
 #ifdef __cplusplus
 }
 #endif

@@ -23,6 +23,7 @@ HM_EDEVICE = -4
 HM_EINTERNAL = -5
 HM_MEM_HOST = 0
 HM_MEM_DEVICE = 1
+HM_OPT_BITSET_MAX_NODES = 1
 
 _ERROR_NAMES = {HM_EINVAL: "HM_EINVAL", HM_EUNSUPPORTED: "HM_EUNSUPPORTED", HM_ENOMEM: "HM_ENOMEM",
                 HM_EDEVICE: "HM_EDEVICE", HM_EINTERNAL: "HM_EINTERNAL"}
@@ -58,6 +59,11 @@ SIGNATURES = {
     "hm_graph_stats": (_int, [_vp, _vp]),
     "hm_graph_export": (_int, [_vp, _int, _vp]),
     "count_exact": (_int, [_vp, _int, _vp, _vp]),
+    "hm_set_option": (_int, [_int, ctypes.c_int64]),
+    "hm_get_option": (_int, [_int, _vp]),
+    "hm_profile_enable": (_int, [_int]),
+    "hm_profile_reset": (_int, []),
+    "hm_profile_read": (_int, [_int, _vp, _vp, _vp]),
 }
 
 
@@ -196,3 +202,35 @@ def count_exact(H: Graph, k: int, out=None, stream=None):
         out = torch.empty(n, dtype=torch.int64, device="cuda")
     _check(lib().count_exact(H.handle, k, ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)))
     return out
+
+
+def hm_profile_enable(on: bool = True) -> None:
+    _check(lib().hm_profile_enable(1 if on else 0))
+
+
+def hm_profile_reset() -> None:
+    _check(lib().hm_profile_reset())
+
+
+def hm_profile_read(max_entries: int = 64) -> dict:
+    """{kernel name: (launches, total milliseconds)} since the last reset."""
+    names = ctypes.create_string_buffer(64 * max_entries)
+    launches = (ctypes.c_uint64 * max_entries)()
+    ms = (ctypes.c_double * max_entries)()
+    n = _check(lib().hm_profile_read(max_entries, names, launches, ms))
+    raw = names.raw
+    out = {}
+    for i in range(n):
+        name = raw[64 * i:64 * (i + 1)].split(b"\0", 1)[0].decode()
+        out[name] = (int(launches[i]), float(ms[i]))
+    return out
+
+
+def hm_set_option(option: int, value: int) -> None:
+    _check(lib().hm_set_option(option, int(value)))
+
+
+def hm_get_option(option: int) -> int:
+    v = ctypes.c_int64()
+    _check(lib().hm_get_option(option, ctypes.byref(v)))
+    return v.value

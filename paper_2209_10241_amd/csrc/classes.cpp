@@ -8,6 +8,9 @@
 #include <array>
 #include <cstdarg>
 #include <cstring>
+#include <map>
+#include <unordered_map>
+#include <atomic>
 #include <mutex>
 #include <numeric>
 #include <vector>
@@ -119,6 +122,7 @@ ClassTables build() {
 }
 
 std::mutex g_lut_mutex;
+std::atomic<uint32_t> g_bitset_max_nodes{kBitsetMaxNodes};
 std::vector<uint8_t*> g_device_luts;  // per device: lut4 (2048) + lut3 (16)
 
 }  // namespace
@@ -131,6 +135,8 @@ void set_error(const char* fmt, ...) {
 }
 
 const char* last_error() { return g_err; }
+
+uint32_t bitset_max_nodes() { return g_bitset_max_nodes.load(); }
 
 const ClassTables& class_tables() {
   static const ClassTables t = build();
@@ -159,20 +165,74 @@ int device_luts(int device, const uint8_t** lut4, const uint8_t** lut3) {
   return HM_OK;
 }
 
+// Device memory cache: blocks are rounded up to a power of two and, when
+// released, kept on a free list of their (device, size class) for the next
+// allocation of that class instead of being returned to the runtime.  Every
+// release happens after the work that used the block has been ordered
+// before any later user (the library synchronises its stream before
+// releasing temporaries), so a cached block is never handed out while in use.
+namespace {
+struct BlockInfo {
+  int device;
+  size_t bytes;
+};
+std::mutex g_pool_mu;
+std::map<std::pair<int, size_t>, std::vector<void*>> g_free;
+std::unordered_map<void*, BlockInfo> g_live;
+size_t g_cached_bytes = 0;
+constexpr size_t kMaxCachedBytes = size_t(8) << 30;
+
+size_t size_class(size_t bytes) {
+  size_t c = 256;
+  while (c < bytes) c <<= 1;
+  return c;
+}
+}  // namespace
+
 int dalloc(void** p, size_t bytes) {
   *p = nullptr;
-  if (bytes == 0) bytes = 16;
-  hipError_t e = hipMalloc(p, bytes);
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) {
+    set_error("hipGetDevice failed");
+    return HM_EDEVICE;
+  }
+  const size_t cls = size_class(bytes ? bytes : 1);
+  {
+    std::lock_guard<std::mutex> lock(g_pool_mu);
+    auto it = g_free.find({dev, cls});
+    if (it != g_free.end() && !it->second.empty()) {
+      *p = it->second.back();
+      it->second.pop_back();
+      g_cached_bytes -= cls;
+      g_live[*p] = BlockInfo{dev, cls};
+      return HM_OK;
+    }
+  }
+  hipError_t e = hipMalloc(p, cls);
   if (e != hipSuccess) {
     (void)hipGetLastError();
-    set_error("hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+    *p = nullptr;
+    set_error("hipMalloc(%zu) failed: %s", cls, hipGetErrorString(e));
     return e == hipErrorOutOfMemory ? HM_ENOMEM : HM_EDEVICE;
   }
+  std::lock_guard<std::mutex> lock(g_pool_mu);
+  g_live[*p] = BlockInfo{dev, cls};
   return HM_OK;
 }
 
 void dfree(void* p) {
-  if (p) (void)hipFree(p);
+  if (!p) return;
+  std::lock_guard<std::mutex> lock(g_pool_mu);
+  auto it = g_live.find(p);
+  if (it == g_live.end()) return;
+  const BlockInfo info = it->second;
+  g_live.erase(it);
+  if (g_cached_bytes + info.bytes > kMaxCachedBytes) {
+    (void)hipFree(p);
+    return;
+  }
+  g_free[{info.device, info.bytes}].push_back(p);
+  g_cached_bytes += info.bytes;
 }
 
 }  // namespace hm
@@ -182,6 +242,32 @@ extern "C" {
 const char* hm_last_error(void) { return hm::last_error(); }
 
 const char* hm_version(void) { return "homotif 0.1 (gfx950)"; }
+
+int hm_set_option(int option, int64_t value) {
+  if (option == HM_OPT_BITSET_MAX_NODES) {
+    if (value < 0 || value > int64_t(hm::kBitsetMaxNodes)) {
+      hm::set_error("HM_OPT_BITSET_MAX_NODES must be in [0, %u]", hm::kBitsetMaxNodes);
+      return HM_EINVAL;
+    }
+    hm::g_bitset_max_nodes.store(uint32_t(value));
+    return HM_OK;
+  }
+  hm::set_error("unknown option %d", option);
+  return HM_EINVAL;
+}
+
+int hm_get_option(int option, int64_t* value) {
+  if (!value) {
+    hm::set_error("value is NULL");
+    return HM_EINVAL;
+  }
+  if (option == HM_OPT_BITSET_MAX_NODES) {
+    *value = hm::g_bitset_max_nodes.load();
+    return HM_OK;
+  }
+  hm::set_error("unknown option %d", option);
+  return HM_EINVAL;
+}
 
 int hm_num_classes(int k) {
   if (k != 3 && k != 4) {

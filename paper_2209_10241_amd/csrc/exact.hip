@@ -97,6 +97,23 @@ __device__ inline unsigned long long wave_sum(unsigned long long v) {
   return (unsigned long long)hi << 32 | lo;
 }
 
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+__device__ inline uint32_t wave_exclusive_scan(uint32_t v, uint32_t* total) {
+  const int lane = threadIdx.x & (kWave - 1);
+  uint32_t x = v;
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    const uint32_t y = __shfl_up(x, d, kWave);
+    if (lane >= d) x += y;
+  }
+  *total = __shfl(x, kWave - 1, kWave);
+  return x - v;
+}
+
 __device__ inline void load_lut(uint8_t* lut, const uint8_t* g, int n) {
   for (int i = threadIdx.x; i < n; i += blockDim.x) lut[i] = g[i];
 }
@@ -108,8 +125,13 @@ __device__ inline void flush(unsigned long long* lds, unsigned long long* out, i
 
 // ---------------------------------------------------------------- order 4
 // (a): one thread per 4-node hyperedge; local positions a,b,c,d = 0..3.
+__device__ inline uint32_t pair_bit(const Set64& hs2, const uint32_t* bits, uint32_t W, uint32_t u, uint32_t v) {
+  return bits ? ((bits[uint64_t(u) * W + (v >> 5)] >> (v & 31)) & 1u) : uint32_t(has2(hs2, u, v));
+}
+
 __global__ void __launch_bounds__(kThreads) k_case_a4(const uint32_t* __restrict__ e4, uint64_t n4, Set64 hs2,
-                                                      Set128 hs3, const uint8_t* __restrict__ lut_g,
+                                                      Set128 hs3, const uint32_t* __restrict__ bits, uint32_t W,
+                                                      const uint8_t* __restrict__ lut_g,
                                                       unsigned long long* __restrict__ hist) {
   __shared__ uint8_t lut[2048];
   __shared__ unsigned long long h_main[256], h_sub[256];
@@ -120,14 +142,14 @@ __global__ void __launch_bounds__(kThreads) k_case_a4(const uint32_t* __restrict
   for (uint64_t i = uint64_t(blockIdx.x) * kThreads + threadIdx.x; i < n4; i += uint64_t(gridDim.x) * kThreads) {
     const uint32_t a = e4[4 * i], b = e4[4 * i + 1], c = e4[4 * i + 2], d = e4[4 * i + 3];
     uint32_t p = 1u << 10;
-    p |= uint32_t(has2(hs2, a, b)) << 0;
-    p |= uint32_t(has2(hs2, a, c)) << 1;
-    p |= uint32_t(has2(hs2, b, c)) << 2;
+    p |= pair_bit(hs2, bits, W, a, b) << 0;
+    p |= pair_bit(hs2, bits, W, a, c) << 1;
+    p |= pair_bit(hs2, bits, W, b, c) << 2;
     p |= uint32_t(set128_has(hs3, key3(a, b, c))) << 3;
-    p |= uint32_t(has2(hs2, a, d)) << 4;
-    p |= uint32_t(has2(hs2, b, d)) << 5;
+    p |= pair_bit(hs2, bits, W, a, d) << 4;
+    p |= pair_bit(hs2, bits, W, b, d) << 5;
     p |= uint32_t(set128_has(hs3, key3(a, b, d))) << 6;
-    p |= uint32_t(has2(hs2, c, d)) << 7;
+    p |= pair_bit(hs2, bits, W, c, d) << 7;
     p |= uint32_t(set128_has(hs3, key3(a, c, d))) << 8;
     p |= uint32_t(set128_has(hs3, key3(b, c, d))) << 9;
     atomicAdd(&h_main[lut[p]], 1ull);
@@ -203,16 +225,17 @@ __global__ void __launch_bounds__(kThreads) k_case_b4(
       sort3(x0, x1, x2);
       const uint32_t tab = set128_has(hs3, key3(x0, x1, x2));
       if (src > 3 && tab) continue;
-      if (tab && tri_less(x0, x1, x2, a, b, c)) continue;
+      if (tab && v < c) continue;                       // {a,b,v} precedes e
+
       uint32_t y0 = a, y1 = c, y2 = v;
       sort3(y0, y1, y2);
       const uint32_t tac = set128_has(hs3, key3(y0, y1, y2));
       if (src > 4 && tac) continue;
-      if (tac && tri_less(y0, y1, y2, a, b, c)) continue;
+      if (tac && v < b) continue;                       // {a,c,v} precedes e
       uint32_t z0 = b, z1 = c, z2 = v;
       sort3(z0, z1, z2);
       const uint32_t tbc = set128_has(hs3, key3(z0, z1, z2));
-      if (tbc && tri_less(z0, z1, z2, a, b, c)) continue;
+      if (tbc && v < a) continue;                       // {b,c,v} precedes e
       uint32_t w0 = a, w1 = b, w2 = c, w3 = v;
       if (w3 < w2) { w3 = w2; w2 = v; if (w2 < w1) { w2 = w1; w1 = v; if (w1 < w0) { w1 = w0; w0 = v; } } }
       if (set128_has(hs4, key4(w0, w1, w2, w3))) continue;   // a 4-node hyperedge: owned by (a)
@@ -234,12 +257,27 @@ __global__ void __launch_bounds__(kThreads) k_case_b4(
 //   |A| = 2: x<y neighbours of r, z > r not a neighbour of r, adjacent to x or y
 //   |A| = 1: x the only neighbour of r; y,z > r non-neighbours of r with
 //            {x,y,z} connected: y<z both adjacent to x, or y~x, z~y, z!~x.
-// Lanes run over (y, word) pairs; each word contributes popcounts.
-struct C4Acc {
-  unsigned long long t3[2][4];   // [x~y][ (x~z)*2 + (y~z) ], |A| = 3
-  unsigned long long t2[2][3];   // [x~y][ both, x only, y only ], |A| = 2
-  unsigned long long paw, star, path;  // |A| = 1
-};
+// A row has W words.  With W <= 64 the wavefront is split into 64/W groups of
+// W lanes, lane (g, w) owning word w of every y that group g takes, so the
+// words of r and x and the masks that depend only on r are loaded once per
+// pair; wider rows loop over words.  Each word contributes popcounts of the
+// candidate z it holds, split by the adjacency of z to x and y.
+__device__ inline void c4_word(uint32_t Nr, uint32_t Nx, uint32_t Ny, uint32_t gy, uint32_t wr, bool xy,
+                               unsigned long long (&t3_0)[4], unsigned long long (&t3_1)[4],
+                               unsigned long long (&t2_0)[3], unsigned long long (&t2_1)[3]) {
+  const uint32_t z3 = Nr & gy;
+  const uint32_t z3x = z3 & Nx, z3n = z3 & ~Nx;
+  const uint32_t c11 = __popc(z3x & Ny), c10 = __popc(z3x & ~Ny), c01 = __popc(z3n & Ny), c00 = __popc(z3n & ~Ny);
+  const uint32_t z2 = wr & (Nx | Ny);
+  const uint32_t b2 = __popc(z2 & Nx & Ny), bx = __popc(z2 & Nx & ~Ny), by = __popc(z2 & ~Nx & Ny);
+  if (xy) {
+    t3_1[3] += c11; t3_1[2] += c10; t3_1[1] += c01; t3_1[0] += c00;
+    t2_1[0] += b2; t2_1[1] += bx; t2_1[2] += by;
+  } else {
+    t3_0[3] += c11; t3_0[2] += c10; t3_0[1] += c01; t3_0[0] += c00;
+    t2_0[0] += b2; t2_0[1] += bx; t2_0[2] += by;
+  }
+}
 
 __global__ void __launch_bounds__(kThreads) k_case_c4_bits(
     const uint32_t* __restrict__ e2, uint64_t n2, const uint32_t* __restrict__ g2_off,
@@ -247,6 +285,7 @@ __global__ void __launch_bounds__(kThreads) k_case_c4_bits(
     const uint8_t* __restrict__ lut_g, unsigned long long* __restrict__ hist) {
   __shared__ uint8_t lut[2048];
   __shared__ unsigned long long h_g2[256];
+  __shared__ uint32_t ylist[kWavesPerBlock][kWave];
   load_lut(lut, lut_g, 2048);
   h_g2[threadIdx.x] = 0;
   __syncthreads();
@@ -254,52 +293,66 @@ __global__ void __launch_bounds__(kThreads) k_case_c4_bits(
   unsigned long long t2_0[3] = {0, 0, 0}, t2_1[3] = {0, 0, 0};
   unsigned long long paw = 0, star = 0, path = 0;
   const int lane = threadIdx.x & (kWave - 1);
-  const uint64_t wave = uint64_t(blockIdx.x) * kWavesPerBlock + threadIdx.x / kWave;
+  const int wv = threadIdx.x / kWave;
+  uint32_t* ys = ylist[wv];
+  const uint64_t wave = uint64_t(blockIdx.x) * kWavesPerBlock + wv;
   const uint64_t n_waves = uint64_t(gridDim.x) * kWavesPerBlock;
+  const bool grouped = W <= uint32_t(kWave);
+  const uint32_t G = grouped ? uint32_t(kWave) / W : 1u;     // y's in flight per wavefront
+  const uint32_t g = grouped ? uint32_t(lane) / W : 0u;
+  const uint32_t w0 = grouped ? uint32_t(lane) % W : uint32_t(lane);
+  const uint32_t wstep = grouped ? W : uint32_t(kWave);
+  const bool lane_on = grouped ? (g < G) : true;
   for (uint64_t i = wave; i < n2; i += n_waves) {
     const uint32_t r = e2[2 * i], x = e2[2 * i + 1];
     const uint32_t* Rr = bits + uint64_t(r) * W;
     const uint32_t* Rx = bits + uint64_t(x) * W;
-    // |A| = 3 and |A| = 2: y runs over the neighbours of r above x
-    {
-      const uint32_t re = g2_off[r + 1];
-      const uint32_t p = upper_bound(g2_adj, g2_off[r], re, x);
-      const uint32_t tasks = (re - p) * W;
-      for (uint32_t t = lane; t < tasks; t += kWave) {
-        const uint32_t y = g2_adj[p + t / W], w = t % W;
-        const uint32_t Nr = Rr[w], Nx = Rx[w], Ny = bits[uint64_t(y) * W + w];
-        const bool xy = (Rx[y >> 5] >> (y & 31)) & 1u;
-        const uint32_t z3 = Nr & mask_gt(y, w);
-        const uint32_t z3x = z3 & Nx, z3n = z3 & ~Nx;
-        const unsigned long long c11 = __popc(z3x & Ny), c10 = __popc(z3x & ~Ny), c01 = __popc(z3n & Ny),
-                                 c00 = __popc(z3n & ~Ny);
-        const uint32_t wr = ~Nr & mask_gt(r, w) & mask_below(N, w);
-        const uint32_t z2 = wr & (Nx | Ny);
-        const unsigned long long b2 = __popc(z2 & Nx & Ny), bx = __popc(z2 & Nx & ~Ny), by = __popc(z2 & ~Nx & Ny);
-        if (xy) {
-          t3_1[3] += c11; t3_1[2] += c10; t3_1[1] += c01; t3_1[0] += c00;
-          t2_1[0] += b2; t2_1[1] += bx; t2_1[2] += by;
-        } else {
-          t3_0[3] += c11; t3_0[2] += c10; t3_0[1] += c01; t3_0[0] += c00;
-          t2_0[0] += b2; t2_0[1] += bx; t2_0[2] += by;
+    const uint32_t re = g2_off[r + 1];
+    const uint32_t p = upper_bound(g2_adj, g2_off[r], re, x);
+    const uint32_t xe = g2_off[x + 1];
+    const uint32_t q = upper_bound(g2_adj, g2_off[x], xe, r);
+    // |A| = 3 and |A| = 2: y over the neighbours of r above x, 64 at a time
+    for (uint32_t base = p; base < re; base += kWave) {
+      const uint32_t cnt = min(uint32_t(kWave), re - base);
+      if (uint32_t(lane) < cnt) ys[lane] = g2_adj[base + lane];
+      wave_sync();
+      if (lane_on)
+        for (uint32_t w = w0; w < W; w += wstep) {
+          const uint32_t Nr = Rr[w], Nx = Rx[w];
+          const uint32_t wr = ~Nr & mask_gt(r, w) & mask_below(N, w);
+          for (uint32_t j = g; j < cnt; j += G) {
+            const uint32_t y = ys[j];
+            const uint32_t Ny = bits[uint64_t(y) * W + w];
+            const bool xy = (Rx[y >> 5] >> (y & 31)) & 1u;
+            c4_word(Nr, Nx, Ny, mask_gt(y, w), wr, xy, t3_0, t3_1, t2_0, t2_1);
+          }
         }
-      }
+      wave_sync();
     }
-    // |A| = 1: y runs over the neighbours of x above r that are not neighbours of r
-    {
-      const uint32_t xe = g2_off[x + 1];
-      const uint32_t q = upper_bound(g2_adj, g2_off[x], xe, r);
-      const uint32_t tasks = (xe - q) * W;
-      for (uint32_t t = lane; t < tasks; t += kWave) {
-        const uint32_t y = g2_adj[q + t / W], w = t % W;
-        if ((Rr[y >> 5] >> (y & 31)) & 1u) continue;
-        const uint32_t Nr = Rr[w], Nx = Rx[w], Ny = bits[uint64_t(y) * W + w];
-        const uint32_t wr = ~Nr & mask_gt(r, w) & mask_below(N, w);
-        const uint32_t zz = Nx & wr & mask_gt(y, w);
-        paw += __popc(zz & Ny);
-        star += __popc(zz & ~Ny);
-        path += __popc(Ny & wr & ~Nx);
-      }
+    // |A| = 1: y over the neighbours of x above r that are not neighbours of r
+    for (uint32_t base = q; base < xe; base += kWave) {
+      const bool in = base + lane < xe;
+      const uint32_t y0 = in ? g2_adj[base + lane] : 0u;
+      const bool keep = in && !((Rr[y0 >> 5] >> (y0 & 31)) & 1u);
+      const unsigned long long mk = __ballot(keep);
+      const uint32_t cnt = uint32_t(__popcll(mk));
+      if (keep) ys[__popcll(mk & ((1ull << lane) - 1ull))] = y0;
+      wave_sync();
+      if (lane_on)
+        for (uint32_t w = w0; w < W; w += wstep) {
+          const uint32_t Nr = Rr[w], Nx = Rx[w];
+          const uint32_t wr = ~Nr & mask_gt(r, w) & mask_below(N, w);
+          const uint32_t nxw = Nx & wr;
+          for (uint32_t j = g; j < cnt; j += G) {
+            const uint32_t y = ys[j];
+            const uint32_t Ny = bits[uint64_t(y) * W + w];
+            const uint32_t zz = nxw & mask_gt(y, w);
+            paw += __popc(zz & Ny);
+            star += __popc(zz & ~Ny);
+            path += __popc(Ny & wr & ~Nx);
+          }
+        }
+      wave_sync();
     }
   }
   // local positions r=0, x=1, y=2, z=3; pair bits: rx 0, ry 1, xy 2, rz 4, xz 5, yz 7
@@ -324,11 +377,120 @@ __global__ void __launch_bounds__(kThreads) k_case_c4_bits(
   v[15] = star; pat[15] = (1u << 0) | (1u << 2) | (1u << 5);
   v[16] = path; pat[16] = (1u << 0) | (1u << 2) | (1u << 7);
   for (int j = 0; j < 17; ++j) {
-    const unsigned long long s = wave_sum(v[j]);
-    if (lane == 0 && s) atomicAdd(&h_g2[lut[pat[j]]], s);
+    const unsigned long long sum = wave_sum(v[j]);
+    if (lane == 0 && sum) atomicAdd(&h_g2[lut[pat[j]]], sum);
   }
   __syncthreads();
   flush(h_g2, hist + kG2, 256);
+}
+
+// (b) with adjacency bit rows: one wavefront per 3-node hyperedge e = {a<b<c}.
+// The wavefront first builds, in LDS, bit sets of the nodes v for which
+// {a,b,v}, {a,c,v}, {b,c,v} are 3-node hyperedges (from the incident 3-node
+// hyperedges of a and b) and for which e u {v} is a 4-node hyperedge (from the
+// incident 4-node hyperedges of a).  The candidates are the union of these
+// with the pairwise neighbours of a, b and c, compacted with popcount prefix
+// sums so that every v is taken once; fill-in of e u {v} is then a set of bit
+// tests.  e counts e u {v} when no other 3-node hyperedge inside it precedes
+// e and it is not a 4-node hyperedge.
+constexpr uint32_t kMaxWordsB = kBitsetMaxNodes / 32;
+constexpr int kChunkWords = kWave;
+
+__global__ void __launch_bounds__(kThreads) k_case_b4_bits(
+    const uint32_t* __restrict__ e3, uint64_t n3, const uint32_t* __restrict__ e4,
+    const uint32_t* __restrict__ i3_off, const uint32_t* __restrict__ i3_idx, const uint32_t* __restrict__ i4_off,
+    const uint32_t* __restrict__ i4_idx, const uint32_t* __restrict__ bits, uint32_t W,
+    const uint8_t* __restrict__ lut_g, unsigned long long* __restrict__ hist) {
+  __shared__ uint8_t lut[2048];
+  __shared__ unsigned long long h_main[256], h_sub[256];
+  __shared__ uint32_t sets[kWavesPerBlock][4][kMaxWordsB];      // T_ab, T_ac, T_bc, Q
+  __shared__ uint32_t cand[kWavesPerBlock][kChunkWords * 32];
+  load_lut(lut, lut_g, 2048);
+  h_main[threadIdx.x] = 0;
+  h_sub[threadIdx.x] = 0;
+  __syncthreads();
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wv = threadIdx.x / kWave;
+  uint32_t* Tab = sets[wv][0];
+  uint32_t* Tac = sets[wv][1];
+  uint32_t* Tbc = sets[wv][2];
+  uint32_t* Q = sets[wv][3];
+  uint32_t* list = cand[wv];
+  const uint64_t wave = uint64_t(blockIdx.x) * kWavesPerBlock + wv;
+  const uint64_t n_waves = uint64_t(gridDim.x) * kWavesPerBlock;
+  for (uint64_t i = wave; i < n3; i += n_waves) {
+    const uint32_t a = e3[3 * i], b = e3[3 * i + 1], c = e3[3 * i + 2];
+    const uint32_t* Ra = bits + uint64_t(a) * W;
+    const uint32_t* Rb = bits + uint64_t(b) * W;
+    const uint32_t* Rc = bits + uint64_t(c) * W;
+    for (uint32_t w = lane; w < W; w += kWave) {
+      Tab[w] = 0; Tac[w] = 0; Tbc[w] = 0; Q[w] = 0;
+    }
+    wave_sync();
+    // 3-node hyperedges sharing two nodes with e
+    const uint32_t pa = i3_off[a], la = i3_off[a + 1] - pa;
+    const uint32_t pb = i3_off[b], lb = i3_off[b + 1] - pb;
+    for (uint32_t t = lane; t < la + lb; t += kWave) {
+      const uint32_t f = i3_idx[t < la ? pa + t : pb + (t - la)];
+      const uint32_t x = e3[3ull * f], y = e3[3ull * f + 1], z = e3[3ull * f + 2];
+      const bool ha = (x == a || y == a || z == a), hb = (x == b || y == b || z == b), hc = (x == c || y == c || z == c);
+      if (int(ha) + int(hb) + int(hc) != 2) continue;
+      const uint32_t v = (x != a && x != b && x != c) ? x : ((y != a && y != b && y != c) ? y : z);
+      uint32_t* T = (ha && hb) ? Tab : (ha ? Tac : Tbc);
+      atomicOr(&T[v >> 5], 1u << (v & 31));
+    }
+    // 4-node hyperedges containing e
+    const uint32_t p4 = i4_off[a], l4 = i4_off[a + 1] - p4;
+    for (uint32_t t = lane; t < l4; t += kWave) {
+      const uint32_t f = i4_idx[p4 + t];
+      uint32_t m[4] = {e4[4ull * f], e4[4ull * f + 1], e4[4ull * f + 2], e4[4ull * f + 3]};
+      int hits = 0;
+      uint32_t v = 0;
+      for (int j = 0; j < 4; ++j) {
+        if (m[j] == a || m[j] == b || m[j] == c) ++hits; else v = m[j];
+      }
+      if (hits == 3) atomicOr(&Q[v >> 5], 1u << (v & 31));
+    }
+    wave_sync();
+    const uint32_t pab = (Ra[b >> 5] >> (b & 31)) & 1u, pac = (Ra[c >> 5] >> (c & 31)) & 1u,
+                   pbc = (Rb[c >> 5] >> (c & 31)) & 1u;
+    const uint32_t base_p = pab | (pac << 1) | (pbc << 2) | (1u << 3);
+    for (uint32_t w0 = 0; w0 < W; w0 += kChunkWords) {
+      const uint32_t w = w0 + lane;
+      uint32_t cw = 0;
+      if (w < W) {
+        cw = Ra[w] | Rb[w] | Rc[w] | Tab[w] | Tac[w] | Tbc[w];
+        if ((a >> 5) == w) cw &= ~(1u << (a & 31));
+        if ((b >> 5) == w) cw &= ~(1u << (b & 31));
+        if ((c >> 5) == w) cw &= ~(1u << (c & 31));
+      }
+      uint32_t total;
+      uint32_t pos = wave_exclusive_scan(__popc(cw), &total);
+      while (cw) {
+        const uint32_t bit = __ffs(cw) - 1;
+        cw &= cw - 1;
+        list[pos++] = (w << 5) | bit;
+      }
+      wave_sync();
+      for (uint32_t t = lane; t < total; t += kWave) {
+        const uint32_t v = list[t];
+        const uint32_t vw = v >> 5, vb = v & 31;
+        if ((Q[vw] >> vb) & 1u) continue;                    // a 4-node hyperedge: owned by (a)
+        const uint32_t tab = (Tab[vw] >> vb) & 1u, tac = (Tac[vw] >> vb) & 1u, tbc = (Tbc[vw] >> vb) & 1u;
+        if ((tab && v < c) || (tac && v < b) || (tbc && v < a)) continue;   // an earlier 3-node hyperedge
+        const uint32_t qa = (Ra[vw] >> vb) & 1u, qb = (Rb[vw] >> vb) & 1u, qc = (Rc[vw] >> vb) & 1u;
+        // local positions a=0, b=1, c=2, v=3
+        const uint32_t pt = base_p | (qa << 4) | (qb << 5) | (tab << 6) | (qc << 7) | (tac << 8) | (tbc << 9);
+        atomicAdd(&h_main[lut[pt]], 1ull);
+        const uint8_t gsh = lut[pt & kPairBits4];
+        if (gsh != 0xFF) atomicAdd(&h_sub[gsh], 1ull);
+      }
+      wave_sync();
+    }
+  }
+  __syncthreads();
+  flush(h_main, hist + kMain, 256);
+  flush(h_sub, hist + kSub, 256);
 }
 
 // (c) without bit rows: the same shapes enumerated one set at a time with
@@ -400,6 +562,7 @@ __global__ void __launch_bounds__(kThreads) k_case_c4_hash(
 // ---------------------------------------------------------------- order 3
 // (a): one thread per 3-node hyperedge; local positions a,b,c = 0,1,2.
 __global__ void __launch_bounds__(kThreads) k_case_a3(const uint32_t* __restrict__ e3, uint64_t n3, Set64 hs2,
+                                                      const uint32_t* __restrict__ bits, uint32_t W,
                                                       const uint8_t* __restrict__ lut_g,
                                                       unsigned long long* __restrict__ hist) {
   __shared__ uint8_t lut[16];
@@ -410,8 +573,8 @@ __global__ void __launch_bounds__(kThreads) k_case_a3(const uint32_t* __restrict
   __syncthreads();
   for (uint64_t i = uint64_t(blockIdx.x) * kThreads + threadIdx.x; i < n3; i += uint64_t(gridDim.x) * kThreads) {
     const uint32_t a = e3[3 * i], b = e3[3 * i + 1], c = e3[3 * i + 2];
-    const uint32_t p = (1u << 3) | uint32_t(has2(hs2, a, b)) | (uint32_t(has2(hs2, a, c)) << 1) |
-                       (uint32_t(has2(hs2, b, c)) << 2);
+    const uint32_t p = (1u << 3) | pair_bit(hs2, bits, W, a, b) | (pair_bit(hs2, bits, W, a, c) << 1) |
+                       (pair_bit(hs2, bits, W, b, c) << 2);
     atomicAdd(&h_main[lut[p]], 1ull);
     const uint8_t g = lut[p & kPairBits3];
     if (g != 0xFF) atomicAdd(&h_sub[g], 1ull);
@@ -502,14 +665,19 @@ __global__ void k_combine(const unsigned long long* __restrict__ hist, int n_cla
   counts[c] = int64_t(v);
 }
 
-unsigned grid_waves(uint64_t items, unsigned cap = 8192) {
+// Counting kernels keep per-class counters in LDS and flush them once per
+// workgroup; a grid of a few workgroups per CU that strides over the work
+// keeps those flushes (global atomics on a few hundred addresses) rare.
+constexpr unsigned kCountGrid = 512;
+
+unsigned grid_waves(uint64_t items, unsigned cap = kCountGrid) {
   uint64_t g = (items + kWavesPerBlock - 1) / kWavesPerBlock;
   if (g < 1) g = 1;
   if (g > cap) g = cap;
   return unsigned(g);
 }
-unsigned grid_threads(uint64_t items, unsigned cap = 8192) {
-  uint64_t g = (items + kThreads - 1) / kThreads;
+unsigned grid_threads(uint64_t items, unsigned cap = kCountGrid, unsigned per_block = kThreads) {
+  uint64_t g = (items + per_block - 1) / per_block;
   if (g < 1) g = 1;
   if (g > cap) g = cap;
   return unsigned(g);
@@ -527,26 +695,47 @@ int count_exact_impl(const hm_graph* H, int k, int64_t* counts, hipStream_t st) 
   HM_TRY(fill_u64(H->hist, 0, 4 * 256, st));
   const uint64_t n2 = H->n_by_size[2], n3 = H->n_by_size[3], n4 = H->n_by_size[4];
   if (k == 4) {
-    if (n4) k_case_a4<<<grid_threads(n4), kThreads, 0, st>>>(H->e4, n4, H->hs2, H->hs3, lut4, H->hist);
-    if (n3)
-      k_case_b4<<<grid_waves(n3), kThreads, 0, st>>>(H->e3, n3, H->g2_off, H->g2_adj, H->i3_off, H->i3_idx, H->hs2,
-                                                     H->hs3, H->hs4, lut4, H->hist);
+    if (n4) {
+      ProfileScope ps("k_case_a4", st);
+      k_case_a4<<<grid_threads(n4), kThreads, 0, st>>>(H->e4, n4, H->hs2, H->hs3, H->bits, H->words, lut4,
+                                                       H->hist);
+    }
+    if (n3) {
+      if (H->bits) {
+        ProfileScope ps("k_case_b4_bits", st);
+        k_case_b4_bits<<<grid_waves(n3), kThreads, 0, st>>>(H->e3, n3, H->e4, H->i3_off, H->i3_idx, H->i4_off,
+                                                            H->i4_idx, H->bits, H->words, lut4, H->hist);
+      } else {
+        ProfileScope ps("k_case_b4", st);
+        k_case_b4<<<grid_waves(n3), kThreads, 0, st>>>(H->e3, n3, H->g2_off, H->g2_adj, H->i3_off, H->i3_idx,
+                                                       H->hs2, H->hs3, H->hs4, lut4, H->hist);
+      }
+    }
     if (n2) {
-      if (H->bits)
+      if (H->bits) {
+        ProfileScope ps("k_case_c4_bits", st);
         k_case_c4_bits<<<grid_waves(n2), kThreads, 0, st>>>(H->e2, n2, H->g2_off, H->g2_adj, H->bits, H->words,
                                                             H->n_nodes, lut4, H->hist);
-      else
+      } else {
+        ProfileScope ps("k_case_c4_hash", st);
         k_case_c4_hash<<<grid_waves(n2), kThreads, 0, st>>>(H->e2, n2, H->g2_off, H->g2_adj, H->hs2, lut4, H->hist);
+      }
     }
   } else {
-    if (n3) k_case_a3<<<grid_threads(n3), kThreads, 0, st>>>(H->e3, n3, H->hs2, lut3, H->hist);
+    if (n3) {
+      ProfileScope ps("k_case_a3", st);
+      k_case_a3<<<grid_threads(n3), kThreads, 0, st>>>(H->e3, n3, H->hs2, H->bits, H->words, lut3, H->hist);
+    }
     if (n2) {
-      if (H->bits)
+      if (H->bits) {
+        ProfileScope ps("k_case_c3_bits", st);
         k_case_c3_bits<<<grid_threads(n2 * H->words), kThreads, 0, st>>>(H->e2, n2, H->bits, H->words, H->n_nodes,
                                                                          lut3, H->hist);
-      else
+      } else {
+        ProfileScope ps("k_case_c3_hash", st);
         k_case_c3_hash<<<grid_threads(n2), kThreads, 0, st>>>(H->e2, n2, H->g2_off, H->g2_adj, H->hs2, lut3,
                                                               H->hist);
+      }
     }
   }
   HM_HIP(hipGetLastError());

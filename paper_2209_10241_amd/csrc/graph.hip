@@ -328,7 +328,6 @@ int build_csr_from_incidence(hm_graph* H, const uint32_t* e, uint64_t n, int J, 
     HM_HIP(hipGetLastError());
   }
   HM_HIP(hipMemcpyAsync(max_deg, dmax, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
-  HM_HIP(hipStreamSynchronize(st));
   return HM_OK;
 }
 
@@ -502,7 +501,7 @@ int build(hm_graph* H, const uint32_t* members_in, const uint64_t* offsets_in, u
   uint32_t max_deg4 = 0;
   HM_TRY(build_csr_from_incidence(H, H->e4, n4, 4, &H->i4_off, &H->i4_idx, &max_deg4, st));
 
-  if (H->n_nodes <= kBitsetMaxNodes) {
+  if (H->n_nodes <= bitset_max_nodes()) {
     H->words = (H->n_nodes + 31) / 32;
     const uint64_t nw = uint64_t(H->n_nodes) * H->words;
     HM_TRY(owned(&H->bits, nw));

@@ -18,8 +18,10 @@ namespace hm {
 constexpr int kWave = 64;
 constexpr uint32_t kEmpty32 = 0xFFFFFFFFu;
 constexpr unsigned long long kEmpty64 = ~0ull;
-// adjacency bit rows are kept when the node count is at most this
+// adjacency bit rows are kept when the node count is at most this (the
+// largest value HM_OPT_BITSET_MAX_NODES accepts)
 constexpr uint32_t kBitsetMaxNodes = 8192;
+uint32_t bitset_max_nodes();
 
 // ----------------------------------------------------------------- errors
 void set_error(const char* fmt, ...);
@@ -136,6 +138,24 @@ int radix_sort_pairs(unsigned long long* keys, uint32_t* vals, unsigned long lon
                      uint32_t* vals_tmp, uint64_t n, int bits, hipStream_t stream);
 int fill_u32(uint32_t* p, uint32_t value, uint64_t n, hipStream_t stream);
 int fill_u64(unsigned long long* p, unsigned long long value, uint64_t n, hipStream_t stream);
+
+// ----------------------------------------------------------------- profiling
+// While hm_profile_enable(1) is in effect, a scope records HIP events around
+// the launches it encloses on `st`, under `name`.
+bool profiling();
+class ProfileScope {
+ public:
+  ProfileScope(const char* name, hipStream_t st);
+  ~ProfileScope();
+  ProfileScope(const ProfileScope&) = delete;
+  ProfileScope& operator=(const ProfileScope&) = delete;
+
+ private:
+  const char* name_;
+  hipStream_t st_;
+  hipEvent_t start_{}, stop_{};
+  bool active_ = false;
+};
 
 // ----------------------------------------------------------------- device allocations
 int dalloc(void** p, size_t bytes);

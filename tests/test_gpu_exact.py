@@ -21,9 +21,14 @@ def hm():
     return hm
 
 
-def _gpu_counts(hm, h, k):
-    with hm.hm_graph_create(h.members, h.offsets, h.n_nodes) as g:
-        return hm.count_exact(g, k).cpu().numpy()
+def _gpu_counts(hm, h, k, bit_rows=True):
+    """Counts through the C ABI; bit_rows=False forces the hash-probe kernels."""
+    hm.hm_set_option(hm.HM_OPT_BITSET_MAX_NODES, 8192 if bit_rows else 0)
+    try:
+        with hm.hm_graph_create(h.members, h.offsets, h.n_nodes) as g:
+            return hm.count_exact(g, k).cpu().numpy()
+    finally:
+        hm.hm_set_option(hm.HM_OPT_BITSET_MAX_NODES, 8192)
 
 
 def _golden(name, k):
@@ -45,14 +50,15 @@ def test_ingest_strata_match_oracle(hm):
             assert np.array_equal(g.export(j).astype(np.int64), nh.edges(j))
 
 
+@pytest.mark.parametrize("bit_rows", [True, False], ids=["bits", "hash"])
 @pytest.mark.parametrize("seed", range(40))
-def test_random_small_matches_oracle(hm, seed):
+def test_random_small_matches_oracle(hm, seed, bit_rows):
     mixes = [{2: 0.6, 3: 0.3, 4: 0.1}, {1: 0.05, 2: 0.45, 3: 0.3, 4: 0.15, 5: 0.05}, {2: 0.2, 3: 0.5, 4: 0.3},
              {2: 1.0}, {3: 0.5, 4: 0.5}]
     n = 12 + (seed * 7) % 60
     h = W.random_small(1000 + seed, n, 20 + (seed * 37) % 400, mixes[seed % len(mixes)], allow_dups=bool(seed % 3))
     for k in (3, 4):
-        assert np.array_equal(_gpu_counts(hm, h, k), core.count_exact(h, k)), (seed, k)
+        assert np.array_equal(_gpu_counts(hm, h, k, bit_rows), core.count_exact(h, k)), (seed, k)
 
 
 def test_hand_examples(hm, golden_dir):
@@ -61,18 +67,21 @@ def test_hand_examples(hm, golden_dir):
     for ex in examples:
         h = W.from_lists(ex["edges"], ex["n_nodes"])
         for k in (3, 4):
-            assert np.array_equal(_gpu_counts(hm, h, k), core.count_exact(h, k)), ex["name"]
+            for bit_rows in (True, False):
+                assert np.array_equal(_gpu_counts(hm, h, k, bit_rows), core.count_exact(h, k)), ex["name"]
 
 
-def test_facetoface_order3_workload(hm):
+@pytest.mark.parametrize("bit_rows", [True, False], ids=["bits", "hash"])
+def test_facetoface_order3_workload(hm, bit_rows):
     h = W.cfg0_facetoface_k3(0)
-    assert np.array_equal(_gpu_counts(hm, h, 3), _golden("facetoface_N200_E2000", 3))
+    assert np.array_equal(_gpu_counts(hm, h, 3, bit_rows), _golden("facetoface_N200_E2000", 3))
 
 
-def test_facetoface_order4_workload(hm):
+@pytest.mark.parametrize("bit_rows", [True, False], ids=["bits", "hash"])
+def test_facetoface_order4_workload(hm, bit_rows):
     """The benchmark's workload: N=400, 30,000 hyperedges, k=4."""
     h = W.cfg1_facetoface_k4(0)
-    assert np.array_equal(_gpu_counts(hm, h, 4), _golden("facetoface_N400_E30000", 4))
+    assert np.array_equal(_gpu_counts(hm, h, 4, bit_rows), _golden("facetoface_N400_E30000", 4))
 
 
 def test_facetoface_order4_relabelled(hm):
@@ -83,7 +92,7 @@ def test_facetoface_order4_relabelled(hm):
 
 
 @pytest.mark.parametrize("seed", range(3))
-def test_large_node_ids_use_hash_path(hm, seed):
+def test_large_node_ids(hm, seed):
     """More nodes than the adjacency bit rows allow: pairs are probed in the hash set."""
     base = W.random_small(2000 + seed, 60, 500, {2: 0.6, 3: 0.3, 4: 0.1})
     rng = np.random.default_rng(seed)
@@ -123,3 +132,19 @@ def test_invalid_inputs(hm, edges, n):
 def test_empty_hyperedge_is_rejected(hm):
     with pytest.raises(hm.HMError):
         hm.hm_graph_create(np.array([0, 1], np.uint32), np.array([0, 2, 2], np.uint64), 3)
+
+
+def test_wide_bit_rows(hm):
+    """More than 64 words per bit row (N > 2048): the word loop of the pairs-only kernel."""
+    base = W.random_small(3000, 80, 900, {2: 0.6, 3: 0.3, 4: 0.1})
+    ids = np.sort(np.random.default_rng(9).choice(8000, size=80, replace=False))
+    h = W.Hypergraph(8000, ids[base.members.astype(np.int64)].astype(np.uint32), base.offsets.copy())
+    for k in (3, 4):
+        assert np.array_equal(_gpu_counts(hm, h, k), core.count_exact(h, k)), k
+
+
+def test_bit_row_option_bounds(hm):
+    with pytest.raises(hm.HMError):
+        hm.hm_set_option(hm.HM_OPT_BITSET_MAX_NODES, 8193)
+    with pytest.raises(hm.HMError):
+        hm.hm_set_option(99, 0)
