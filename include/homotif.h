@@ -117,6 +117,50 @@ int hm_graph_export(const hm_graph* H, int j, uint32_t* out);
  * overwritten.  Asynchronous on `stream`. */
 int count_exact(const hm_graph* H, int k, int64_t* counts, void* stream);
 
+/* ---------------------------------------------------------------- sampled */
+
+/* Sample allocation over strata (Section 5: S_j draws from the hyperedges of
+ * size j, with replacement).
+ *   HM_ALLOC_PROPORTIONAL  S_j = ceil(fraction * |E_j|) for j = 2..k
+ *   HM_ALLOC_PAPER         k = 4: S = ceil(fraction * (|E_2|+|E_3|+|E_4|)),
+ *                          S_2 = floor(S/6), S_3 = floor(S/2), S_4 = the rest
+ *                          (the ratio S_3 = 3 S_2, S_4 = 2 S_2 of the
+ *                          appendix's parameter search); k = 3: proportional.
+ * A stratum with no hyperedge gets no sample. */
+#define HM_ALLOC_PROPORTIONAL 0
+#define HM_ALLOC_PAPER 1
+
+/* Sample sizes S_2, S_3, S_4 (host array of 3) for the given fraction in
+ * (0, 1] and allocation; S_4 = 0 when k = 3. */
+int hm_sample_sizes(const hm_graph* H, int k, double fraction, int allocation, uint64_t* s_out);
+
+/* Write the drawn stratum indices (device uint32 arrays of S_2, S_3, S_4
+ * values; pointers for empty strata may be NULL).  Draw i of stratum j is
+ * hi64(w * |E_j|) with w the first word of Philox4x64-10 (Salmon et al.,
+ * SC'11) at counter (i, 0, 0, 0) under key (seed, (1 << 32) | j).
+ * Asynchronous on `stream`. */
+int hm_sample_draw(const hm_graph* H, int k, double fraction, uint64_t seed, int allocation, uint32_t* idx2,
+                   uint32_t* idx3, uint32_t* idx4, void* stream);
+
+/* Sampled counts (Algorithm 4): draw the samples as hm_sample_draw does;
+ * around every sampled hyperedge e enumerate the connected k-node sets that
+ * contain e and hold no hyperedge larger than e, adding one to their class;
+ * scale class m by |E_maxcard| / (S_maxcard * countmax) (the correction factor
+ * of Algorithm 4; unbiased by Section 5's argument), in fp64 rounded once to
+ * fp32.
+ *   est  device float array of hm_num_classes(k) values (required)
+ *   raw  device int64 array of the unscaled counts, or NULL
+ * fraction in (0, 1]; HM_EINVAL otherwise.  Asynchronous on `stream`. */
+int count_sampled(const hm_graph* H, int k, double fraction, uint64_t seed, int allocation, float* est,
+                  int64_t* raw, void* stream);
+
+/* The same on an explicit sample: device uint32 arrays of stratum indices
+ * (repetitions allowed), s_j entries each; a NULL array needs s_j = 0; idx4
+ * is ignored for k = 3.  HM_EINVAL when an index lies outside its stratum
+ * (checked before counting; this call synchronises the stream once). */
+int count_sampled_indices(const hm_graph* H, int k, const uint32_t* idx2, uint64_t s2, const uint32_t* idx3,
+                          uint64_t s3, const uint32_t* idx4, uint64_t s4, float* est, int64_t* raw, void* stream);
+
 /* ---------------------------------------------------------------- options */
 
 /* Process-wide tuning options (read when a graph is created).

@@ -142,3 +142,25 @@ def class_canon_c(k: int) -> list:
 
 def pattern_class_c(k: int, pattern: int) -> int:
     return lib().oracle_pattern_class(k, pattern)
+
+
+ALLOC_PROPORTIONAL = 0
+ALLOC_PAPER = 1
+
+
+def sample_sizes(n_by_size: dict, k: int, fraction: float, allocation: int = ALLOC_PROPORTIONAL) -> dict:
+    """Number of draws per stratum (Section 5: S_j samples from the hyperedges of size j).
+
+    Proportional: S_j = ceil(fraction * |E_j|).  Paper split for k = 4
+    (appendix: S_3 = 3 S_2, S_4 = 2 S_2): S = ceil(fraction * sum_j |E_j|),
+    S_2 = floor(S / 6), S_3 = floor(S / 2), S_4 = S - S_2 - S_3.  An empty
+    stratum gets no draw.
+    """
+    import math
+    if allocation == ALLOC_PAPER and k == 4:
+        s = math.ceil(fraction * float(sum(n_by_size.get(j, 0) for j in (2, 3, 4))))
+        S = {2: s // 6, 3: s // 2}
+        S[4] = s - S[2] - S[3]
+    else:
+        S = {j: math.ceil(fraction * float(n_by_size.get(j, 0))) for j in range(2, k + 1)}
+    return {j: (S.get(j, 0) if n_by_size.get(j, 0) > 0 else 0) for j in range(2, k + 1)}

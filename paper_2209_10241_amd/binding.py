@@ -24,6 +24,8 @@ HM_EINTERNAL = -5
 HM_MEM_HOST = 0
 HM_MEM_DEVICE = 1
 HM_OPT_BITSET_MAX_NODES = 1
+HM_ALLOC_PROPORTIONAL = 0
+HM_ALLOC_PAPER = 1
 
 _ERROR_NAMES = {HM_EINVAL: "HM_EINVAL", HM_EUNSUPPORTED: "HM_EUNSUPPORTED", HM_ENOMEM: "HM_ENOMEM",
                 HM_EDEVICE: "HM_EDEVICE", HM_EINTERNAL: "HM_EINTERNAL"}
@@ -59,6 +61,10 @@ SIGNATURES = {
     "hm_graph_stats": (_int, [_vp, _vp]),
     "hm_graph_export": (_int, [_vp, _int, _vp]),
     "count_exact": (_int, [_vp, _int, _vp, _vp]),
+    "hm_sample_sizes": (_int, [_vp, _int, _dbl, _int, _vp]),
+    "hm_sample_draw": (_int, [_vp, _int, _dbl, _u64, _int, _vp, _vp, _vp, _vp]),
+    "count_sampled": (_int, [_vp, _int, _dbl, _u64, _int, _vp, _vp, _vp]),
+    "count_sampled_indices": (_int, [_vp, _int, _vp, _u64, _vp, _u64, _vp, _u64, _vp, _vp, _vp]),
     "hm_set_option": (_int, [_int, ctypes.c_int64]),
     "hm_get_option": (_int, [_int, _vp]),
     "hm_profile_enable": (_int, [_int]),
@@ -234,3 +240,62 @@ def hm_get_option(option: int) -> int:
     v = ctypes.c_int64()
     _check(lib().hm_get_option(option, ctypes.byref(v)))
     return v.value
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None and t.numel() else ctypes.c_void_p(0)
+
+
+def hm_sample_sizes(H: Graph, k: int, fraction: float, allocation: int = HM_ALLOC_PROPORTIONAL):
+    out = (ctypes.c_uint64 * 3)()
+    _check(lib().hm_sample_sizes(H.handle, k, float(fraction), allocation, out))
+    return {2: int(out[0]), 3: int(out[1]), 4: int(out[2])}
+
+
+def hm_sample_draw(H: Graph, k: int, fraction: float, seed: int, allocation: int = HM_ALLOC_PROPORTIONAL,
+                   stream=None) -> dict:
+    """Drawn stratum indices {j: uint32 tensor on the device}."""
+    import torch
+    S = hm_sample_sizes(H, k, fraction, allocation)
+    out = {j: torch.empty(S[j], dtype=torch.int32, device="cuda") for j in (2, 3, 4)}
+    _check(lib().hm_sample_draw(H.handle, k, float(fraction), int(seed) & (2**64 - 1), allocation,
+                                _ptr(out[2]), _ptr(out[3]), _ptr(out[4]), _stream_ptr(stream)))
+    return out
+
+
+def count_sampled(H: Graph, k: int, fraction: float, seed: int, allocation: int = HM_ALLOC_PROPORTIONAL,
+                  est=None, raw=None, stream=None):
+    """(estimates fp32, raw int64) torch tensors on the current device."""
+    import torch
+    n = hm_num_classes(k)
+    if est is None:
+        est = torch.empty(n, dtype=torch.float32, device="cuda")
+    if raw is None:
+        raw = torch.empty(n, dtype=torch.int64, device="cuda")
+    _check(lib().count_sampled(H.handle, k, float(fraction), int(seed) & (2**64 - 1), allocation,
+                               ctypes.c_void_p(est.data_ptr()), ctypes.c_void_p(raw.data_ptr()),
+                               _stream_ptr(stream)))
+    return est, raw
+
+
+def count_sampled_indices(H: Graph, k: int, samples: dict, est=None, raw=None, stream=None):
+    """samples: {j: int tensor/array of stratum indices}; returns (est, raw)."""
+    import torch
+    n = hm_num_classes(k)
+    if est is None:
+        est = torch.empty(n, dtype=torch.float32, device="cuda")
+    if raw is None:
+        raw = torch.empty(n, dtype=torch.int64, device="cuda")
+    dev = {}
+    for j in (2, 3, 4):
+        v = samples.get(j)
+        if v is None:
+            dev[j] = None
+            continue
+        t = torch.as_tensor(np.asarray(v) if not isinstance(v, torch.Tensor) else v)
+        dev[j] = t.to(device="cuda", dtype=torch.int32).contiguous()
+    size = {j: (dev[j].numel() if dev[j] is not None else 0) for j in (2, 3, 4)}
+    _check(lib().count_sampled_indices(H.handle, k, _ptr(dev[2]), size[2], _ptr(dev[3]), size[3], _ptr(dev[4]),
+                                       size[4], ctypes.c_void_p(est.data_ptr()), ctypes.c_void_p(raw.data_ptr()),
+                                       _stream_ptr(stream)))
+    return est, raw

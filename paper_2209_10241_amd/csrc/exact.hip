@@ -24,111 +24,18 @@
 // are flushed to device memory with one atomic per class per workgroup.
 #include <vector>
 
-#include "hm_internal.h"
+#include "hm_b4.h"
 
 namespace hm {
 namespace {
 
-constexpr int kThreads = 256;
-constexpr int kWavesPerBlock = kThreads / kWave;
 // histogram regions (256 counters each) in hm_graph::hist
 constexpr int kMain = 0;    // classes counted by (a) and (b)
 constexpr int kSub = 256;   // G2 shape of G2-connected sets counted by (a) and (b)
 constexpr int kG2 = 512;    // G2 shape counts of all connected 4-node (3-node) sets of G2
-// pattern bits of the pairs among 4 local nodes: masks 3,5,6,9,10,12 -> bits 0,1,2,4,5,7
-constexpr uint32_t kPairBits4 = (1u << 0) | (1u << 1) | (1u << 2) | (1u << 4) | (1u << 5) | (1u << 7);
-constexpr uint32_t kPairBits3 = 0x7u;
-
-__device__ inline bool has2(const Set64& s, uint32_t u, uint32_t v) {
-  return set64_has(s, u < v ? key2(u, v) : key2(v, u));
-}
-__device__ inline void sort3(uint32_t& a, uint32_t& b, uint32_t& c) {
-  uint32_t t;
-  if (a > b) { t = a; a = b; b = t; }
-  if (b > c) { t = b; b = c; c = t; }
-  if (a > b) { t = a; a = b; b = t; }
-}
-__device__ inline bool has3(const Set128& s, uint32_t a, uint32_t b, uint32_t c) {
-  sort3(a, b, c);
-  return set128_has(s, key3(a, b, c));
-}
-// lexicographic comparison of ascending triples
-__device__ inline bool tri_less(uint32_t a0, uint32_t a1, uint32_t a2, uint32_t b0, uint32_t b1, uint32_t b2) {
-  if (a0 != b0) return a0 < b0;
-  if (a1 != b1) return a1 < b1;
-  return a2 < b2;
-}
-__device__ inline bool bit_of(const uint32_t* bits, uint32_t words, uint32_t u, uint32_t v) {
-  return (bits[uint64_t(u) * words + (v >> 5)] >> (v & 31)) & 1u;
-}
-// bits of word w whose node index is greater than y
-__device__ inline uint32_t mask_gt(uint32_t y, uint32_t w) {
-  const uint32_t lo = w << 5;
-  if (y < lo) return ~0u;
-  const uint32_t d = y - lo;
-  if (d >= 31) return 0u;
-  return ~0u << (d + 1);
-}
-// bits of word w whose node index is below n
-__device__ inline uint32_t mask_below(uint32_t n, uint32_t w) {
-  const uint32_t lo = w << 5;
-  if (lo + 32 <= n) return ~0u;
-  if (lo >= n) return 0u;
-  return (1u << (n - lo)) - 1u;
-}
-// first position in the ascending row [p, e) whose value is greater than x
-__device__ inline uint32_t upper_bound(const uint32_t* adj, uint32_t p, uint32_t e, uint32_t x) {
-  while (p < e) {
-    uint32_t m = p + ((e - p) >> 1);
-    if (adj[m] <= x) p = m + 1; else e = m;
-  }
-  return p;
-}
-__device__ inline unsigned long long wave_sum(unsigned long long v) {
-  uint32_t lo = uint32_t(v), hi = uint32_t(v >> 32);
-#pragma unroll
-  for (int d = kWave / 2; d > 0; d >>= 1) {
-    uint32_t olo = __shfl_xor(lo, d, kWave);
-    uint32_t ohi = __shfl_xor(hi, d, kWave);
-    unsigned long long s = ((unsigned long long)hi << 32 | lo) + ((unsigned long long)ohi << 32 | olo);
-    lo = uint32_t(s);
-    hi = uint32_t(s >> 32);
-  }
-  return (unsigned long long)hi << 32 | lo;
-}
-
-__device__ inline void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-}
-
-__device__ inline uint32_t wave_exclusive_scan(uint32_t v, uint32_t* total) {
-  const int lane = threadIdx.x & (kWave - 1);
-  uint32_t x = v;
-#pragma unroll
-  for (int d = 1; d < kWave; d <<= 1) {
-    const uint32_t y = __shfl_up(x, d, kWave);
-    if (lane >= d) x += y;
-  }
-  *total = __shfl(x, kWave - 1, kWave);
-  return x - v;
-}
-
-__device__ inline void load_lut(uint8_t* lut, const uint8_t* g, int n) {
-  for (int i = threadIdx.x; i < n; i += blockDim.x) lut[i] = g[i];
-}
-
-__device__ inline void flush(unsigned long long* lds, unsigned long long* out, int n) {
-  for (int i = threadIdx.x; i < n; i += blockDim.x)
-    if (lds[i]) atomicAdd(out + i, lds[i]);
-}
 
 // ---------------------------------------------------------------- order 4
 // (a): one thread per 4-node hyperedge; local positions a,b,c,d = 0..3.
-__device__ inline uint32_t pair_bit(const Set64& hs2, const uint32_t* bits, uint32_t W, uint32_t u, uint32_t v) {
-  return bits ? ((bits[uint64_t(u) * W + (v >> 5)] >> (v & 31)) & 1u) : uint32_t(has2(hs2, u, v));
-}
-
 __global__ void __launch_bounds__(kThreads) k_case_a4(const uint32_t* __restrict__ e4, uint64_t n4, Set64 hs2,
                                                       Set128 hs3, const uint32_t* __restrict__ bits, uint32_t W,
                                                       const uint8_t* __restrict__ lut_g,
@@ -161,10 +68,7 @@ __global__ void __launch_bounds__(kThreads) k_case_a4(const uint32_t* __restrict
   flush(h_sub, hist + kSub, 256);
 }
 
-// (b): one wavefront per 3-node hyperedge e = {a<b<c}.  Generator instances:
-// every pairwise neighbour v of a, b or c (witness 0, 1, 2), and every 3-node
-// hyperedge f sharing exactly two nodes with e, reached from the row of the
-// smaller shared node (witness 3 for {a,b}, 4 for {a,c}, 5 for {b,c}).
+// (b): one wavefront per 3-node hyperedge; see b4_edge_hash / b4_edge_bits.
 __global__ void __launch_bounds__(kThreads) k_case_b4(
     const uint32_t* __restrict__ e3, uint64_t n3, const uint32_t* __restrict__ g2_off,
     const uint32_t* __restrict__ g2_adj, const uint32_t* __restrict__ i3_off, const uint32_t* __restrict__ i3_idx,
@@ -175,77 +79,34 @@ __global__ void __launch_bounds__(kThreads) k_case_b4(
   h_main[threadIdx.x] = 0;
   h_sub[threadIdx.x] = 0;
   __syncthreads();
-  const int lane = threadIdx.x & (kWave - 1);
   const uint64_t wave = uint64_t(blockIdx.x) * kWavesPerBlock + threadIdx.x / kWave;
   const uint64_t n_waves = uint64_t(gridDim.x) * kWavesPerBlock;
-  for (uint64_t i = wave; i < n3; i += n_waves) {
-    const uint32_t a = e3[3 * i], b = e3[3 * i + 1], c = e3[3 * i + 2];
-    const uint32_t pab = has2(hs2, a, b), pac = has2(hs2, a, c), pbc = has2(hs2, b, c);
-    const uint32_t base_p = pab | (pac << 1) | (pbc << 2) | (1u << 3);
-    uint32_t sb[6], sl[6];
-    sb[0] = g2_off[a]; sl[0] = g2_off[a + 1] - sb[0];
-    sb[1] = g2_off[b]; sl[1] = g2_off[b + 1] - sb[1];
-    sb[2] = g2_off[c]; sl[2] = g2_off[c + 1] - sb[2];
-    sb[3] = i3_off[a]; sl[3] = i3_off[a + 1] - sb[3];
-    sb[4] = i3_off[b]; sl[4] = i3_off[b + 1] - sb[4];
-    sl[5] = 0; sb[5] = 0;   // no 3-node hyperedge has c as its smaller node shared with e
-    const uint32_t total = sl[0] + sl[1] + sl[2] + sl[3] + sl[4];
-    for (uint32_t t = lane; t < total; t += kWave) {
-      uint32_t seg = 0, off = t;
-      while (off >= sl[seg]) { off -= sl[seg]; ++seg; }
-      uint32_t v, src;
-      if (seg < 3) {
-        v = g2_adj[sb[seg] + off];
-        if (v == a || v == b || v == c) continue;
-        src = seg;
-      } else {
-        const uint32_t f = i3_idx[sb[seg] + off];
-        const uint32_t x = e3[3ull * f], y = e3[3ull * f + 1], z = e3[3ull * f + 2];
-        const bool xa = (x == a || x == b || x == c), ya = (y == a || y == b || y == c),
-                   za = (z == a || z == b || z == c);
-        if (int(xa) + int(ya) + int(za) != 2) continue;
-        v = !xa ? x : (!ya ? y : z);
-        const bool hasa = (x == a || y == a || z == a), hasb = (x == b || y == b || z == b);
-        if (seg == 3) {
-          if (!hasa) continue;
-          src = hasb ? 3 : 4;          // {a,b,v} or {a,c,v}
-        } else {
-          if (hasa) continue;          // {a,b,v} is taken from a's row
-          src = 5;                     // {b,c,v}
-        }
-      }
-      // fill-in, cheapest witnesses first
-      const uint32_t qa = has2(hs2, a, v);
-      if (src > 0 && qa) continue;
-      const uint32_t qb = has2(hs2, b, v);
-      if (src > 1 && qb) continue;
-      const uint32_t qc = has2(hs2, c, v);
-      if (src > 2 && qc) continue;
-      uint32_t x0 = a, x1 = b, x2 = v;
-      sort3(x0, x1, x2);
-      const uint32_t tab = set128_has(hs3, key3(x0, x1, x2));
-      if (src > 3 && tab) continue;
-      if (tab && v < c) continue;                       // {a,b,v} precedes e
+  for (uint64_t i = wave; i < n3; i += n_waves)
+    b4_edge_hash<true>(e3[3 * i], e3[3 * i + 1], e3[3 * i + 2], e3, g2_off, g2_adj, i3_off, i3_idx, hs2, hs3, hs4,
+                       lut, h_main, h_sub);
+  __syncthreads();
+  flush(h_main, hist + kMain, 256);
+  flush(h_sub, hist + kSub, 256);
+}
 
-      uint32_t y0 = a, y1 = c, y2 = v;
-      sort3(y0, y1, y2);
-      const uint32_t tac = set128_has(hs3, key3(y0, y1, y2));
-      if (src > 4 && tac) continue;
-      if (tac && v < b) continue;                       // {a,c,v} precedes e
-      uint32_t z0 = b, z1 = c, z2 = v;
-      sort3(z0, z1, z2);
-      const uint32_t tbc = set128_has(hs3, key3(z0, z1, z2));
-      if (tbc && v < a) continue;                       // {b,c,v} precedes e
-      uint32_t w0 = a, w1 = b, w2 = c, w3 = v;
-      if (w3 < w2) { w3 = w2; w2 = v; if (w2 < w1) { w2 = w1; w1 = v; if (w1 < w0) { w1 = w0; w0 = v; } } }
-      if (set128_has(hs4, key4(w0, w1, w2, w3))) continue;   // a 4-node hyperedge: owned by (a)
-      // local positions a=0, b=1, c=2, v=3
-      const uint32_t p = base_p | (qa << 4) | (qb << 5) | (tab << 6) | (qc << 7) | (tac << 8) | (tbc << 9);
-      atomicAdd(&h_main[lut[p]], 1ull);
-      const uint8_t g = lut[p & kPairBits4];
-      if (g != 0xFF) atomicAdd(&h_sub[g], 1ull);
-    }
-  }
+__global__ void __launch_bounds__(kThreads) k_case_b4_bits(
+    const uint32_t* __restrict__ e3, uint64_t n3, const uint32_t* __restrict__ e4,
+    const uint32_t* __restrict__ i3_off, const uint32_t* __restrict__ i3_idx, const uint32_t* __restrict__ i4_off,
+    const uint32_t* __restrict__ i4_idx, const uint32_t* __restrict__ bits, uint32_t W,
+    const uint8_t* __restrict__ lut_g, unsigned long long* __restrict__ hist) {
+  __shared__ uint8_t lut[2048];
+  __shared__ unsigned long long h_main[256], h_sub[256];
+  __shared__ B4Scratch scratch[kWavesPerBlock];
+  load_lut(lut, lut_g, 2048);
+  h_main[threadIdx.x] = 0;
+  h_sub[threadIdx.x] = 0;
+  __syncthreads();
+  const int wv = threadIdx.x / kWave;
+  const uint64_t wave = uint64_t(blockIdx.x) * kWavesPerBlock + wv;
+  const uint64_t n_waves = uint64_t(gridDim.x) * kWavesPerBlock;
+  for (uint64_t i = wave; i < n3; i += n_waves)
+    b4_edge_bits<true>(e3[3 * i], e3[3 * i + 1], e3[3 * i + 2], e3, e4, i3_off, i3_idx, i4_off, i4_idx, bits, W,
+                       scratch[wv], lut, h_main, h_sub);
   __syncthreads();
   flush(h_main, hist + kMain, 256);
   flush(h_sub, hist + kSub, 256);
@@ -382,115 +243,6 @@ __global__ void __launch_bounds__(kThreads) k_case_c4_bits(
   }
   __syncthreads();
   flush(h_g2, hist + kG2, 256);
-}
-
-// (b) with adjacency bit rows: one wavefront per 3-node hyperedge e = {a<b<c}.
-// The wavefront first builds, in LDS, bit sets of the nodes v for which
-// {a,b,v}, {a,c,v}, {b,c,v} are 3-node hyperedges (from the incident 3-node
-// hyperedges of a and b) and for which e u {v} is a 4-node hyperedge (from the
-// incident 4-node hyperedges of a).  The candidates are the union of these
-// with the pairwise neighbours of a, b and c, compacted with popcount prefix
-// sums so that every v is taken once; fill-in of e u {v} is then a set of bit
-// tests.  e counts e u {v} when no other 3-node hyperedge inside it precedes
-// e and it is not a 4-node hyperedge.
-constexpr uint32_t kMaxWordsB = kBitsetMaxNodes / 32;
-constexpr int kChunkWords = kWave;
-
-__global__ void __launch_bounds__(kThreads) k_case_b4_bits(
-    const uint32_t* __restrict__ e3, uint64_t n3, const uint32_t* __restrict__ e4,
-    const uint32_t* __restrict__ i3_off, const uint32_t* __restrict__ i3_idx, const uint32_t* __restrict__ i4_off,
-    const uint32_t* __restrict__ i4_idx, const uint32_t* __restrict__ bits, uint32_t W,
-    const uint8_t* __restrict__ lut_g, unsigned long long* __restrict__ hist) {
-  __shared__ uint8_t lut[2048];
-  __shared__ unsigned long long h_main[256], h_sub[256];
-  __shared__ uint32_t sets[kWavesPerBlock][4][kMaxWordsB];      // T_ab, T_ac, T_bc, Q
-  __shared__ uint32_t cand[kWavesPerBlock][kChunkWords * 32];
-  load_lut(lut, lut_g, 2048);
-  h_main[threadIdx.x] = 0;
-  h_sub[threadIdx.x] = 0;
-  __syncthreads();
-  const int lane = threadIdx.x & (kWave - 1);
-  const int wv = threadIdx.x / kWave;
-  uint32_t* Tab = sets[wv][0];
-  uint32_t* Tac = sets[wv][1];
-  uint32_t* Tbc = sets[wv][2];
-  uint32_t* Q = sets[wv][3];
-  uint32_t* list = cand[wv];
-  const uint64_t wave = uint64_t(blockIdx.x) * kWavesPerBlock + wv;
-  const uint64_t n_waves = uint64_t(gridDim.x) * kWavesPerBlock;
-  for (uint64_t i = wave; i < n3; i += n_waves) {
-    const uint32_t a = e3[3 * i], b = e3[3 * i + 1], c = e3[3 * i + 2];
-    const uint32_t* Ra = bits + uint64_t(a) * W;
-    const uint32_t* Rb = bits + uint64_t(b) * W;
-    const uint32_t* Rc = bits + uint64_t(c) * W;
-    for (uint32_t w = lane; w < W; w += kWave) {
-      Tab[w] = 0; Tac[w] = 0; Tbc[w] = 0; Q[w] = 0;
-    }
-    wave_sync();
-    // 3-node hyperedges sharing two nodes with e
-    const uint32_t pa = i3_off[a], la = i3_off[a + 1] - pa;
-    const uint32_t pb = i3_off[b], lb = i3_off[b + 1] - pb;
-    for (uint32_t t = lane; t < la + lb; t += kWave) {
-      const uint32_t f = i3_idx[t < la ? pa + t : pb + (t - la)];
-      const uint32_t x = e3[3ull * f], y = e3[3ull * f + 1], z = e3[3ull * f + 2];
-      const bool ha = (x == a || y == a || z == a), hb = (x == b || y == b || z == b), hc = (x == c || y == c || z == c);
-      if (int(ha) + int(hb) + int(hc) != 2) continue;
-      const uint32_t v = (x != a && x != b && x != c) ? x : ((y != a && y != b && y != c) ? y : z);
-      uint32_t* T = (ha && hb) ? Tab : (ha ? Tac : Tbc);
-      atomicOr(&T[v >> 5], 1u << (v & 31));
-    }
-    // 4-node hyperedges containing e
-    const uint32_t p4 = i4_off[a], l4 = i4_off[a + 1] - p4;
-    for (uint32_t t = lane; t < l4; t += kWave) {
-      const uint32_t f = i4_idx[p4 + t];
-      uint32_t m[4] = {e4[4ull * f], e4[4ull * f + 1], e4[4ull * f + 2], e4[4ull * f + 3]};
-      int hits = 0;
-      uint32_t v = 0;
-      for (int j = 0; j < 4; ++j) {
-        if (m[j] == a || m[j] == b || m[j] == c) ++hits; else v = m[j];
-      }
-      if (hits == 3) atomicOr(&Q[v >> 5], 1u << (v & 31));
-    }
-    wave_sync();
-    const uint32_t pab = (Ra[b >> 5] >> (b & 31)) & 1u, pac = (Ra[c >> 5] >> (c & 31)) & 1u,
-                   pbc = (Rb[c >> 5] >> (c & 31)) & 1u;
-    const uint32_t base_p = pab | (pac << 1) | (pbc << 2) | (1u << 3);
-    for (uint32_t w0 = 0; w0 < W; w0 += kChunkWords) {
-      const uint32_t w = w0 + lane;
-      uint32_t cw = 0;
-      if (w < W) {
-        cw = Ra[w] | Rb[w] | Rc[w] | Tab[w] | Tac[w] | Tbc[w];
-        if ((a >> 5) == w) cw &= ~(1u << (a & 31));
-        if ((b >> 5) == w) cw &= ~(1u << (b & 31));
-        if ((c >> 5) == w) cw &= ~(1u << (c & 31));
-      }
-      uint32_t total;
-      uint32_t pos = wave_exclusive_scan(__popc(cw), &total);
-      while (cw) {
-        const uint32_t bit = __ffs(cw) - 1;
-        cw &= cw - 1;
-        list[pos++] = (w << 5) | bit;
-      }
-      wave_sync();
-      for (uint32_t t = lane; t < total; t += kWave) {
-        const uint32_t v = list[t];
-        const uint32_t vw = v >> 5, vb = v & 31;
-        if ((Q[vw] >> vb) & 1u) continue;                    // a 4-node hyperedge: owned by (a)
-        const uint32_t tab = (Tab[vw] >> vb) & 1u, tac = (Tac[vw] >> vb) & 1u, tbc = (Tbc[vw] >> vb) & 1u;
-        if ((tab && v < c) || (tac && v < b) || (tbc && v < a)) continue;   // an earlier 3-node hyperedge
-        const uint32_t qa = (Ra[vw] >> vb) & 1u, qb = (Rb[vw] >> vb) & 1u, qc = (Rc[vw] >> vb) & 1u;
-        // local positions a=0, b=1, c=2, v=3
-        const uint32_t pt = base_p | (qa << 4) | (qb << 5) | (tab << 6) | (qc << 7) | (tac << 8) | (tbc << 9);
-        atomicAdd(&h_main[lut[pt]], 1ull);
-        const uint8_t gsh = lut[pt & kPairBits4];
-        if (gsh != 0xFF) atomicAdd(&h_sub[gsh], 1ull);
-      }
-      wave_sync();
-    }
-  }
-  __syncthreads();
-  flush(h_main, hist + kMain, 256);
-  flush(h_sub, hist + kSub, 256);
 }
 
 // (c) without bit rows: the same shapes enumerated one set at a time with

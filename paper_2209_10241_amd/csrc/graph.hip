@@ -533,6 +533,7 @@ void release(hm_graph* H) {
   dfree(H->i4_idx);
   dfree(H->bits);
   dfree(H->hist);
+  dfree(H->sample_idx);
 }
 
 }  // namespace

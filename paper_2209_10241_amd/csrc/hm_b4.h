@@ -1,0 +1,195 @@
+// The neighbourhood of one 3-node hyperedge e = {a<b<c} at order 4: every
+// node v that a hyperedge of size 2 or 3 joins to e gives the candidate set
+// e u {v} (Algorithm 3's exploration of "the hyperedges adjacent to e" with
+// |e u e_i| = 4, and Algorithm 4's exploration around a sampled 3-node
+// hyperedge).  A wavefront handles one e; v is taken once.  Sets that are
+// 4-node hyperedges are skipped (their largest hyperedge has 4 nodes).
+//
+// OWN = true (exact counting): e counts e u {v} only if no other 3-node
+// hyperedge inside it precedes e in lexicographic order, so each set is
+// counted by exactly one 3-node hyperedge.  The G2 shape of counted sets
+// whose pairs connect them goes to h_sub.
+// OWN = false (sampling): every sampled e counts every such set.
+#pragma once
+
+#include "hm_device.h"
+
+namespace hm {
+
+constexpr uint32_t kMaxWordsB = kBitsetMaxNodes / 32;
+constexpr int kChunkWords = kWave;
+
+struct B4Scratch {
+  uint32_t sets[4][kMaxWordsB];      // T_ab, T_ac, T_bc, Q
+  uint32_t list[kChunkWords * 32];
+};
+
+__device__ inline void count_class(const uint8_t* lut, unsigned long long* h_main, unsigned long long* h_sub,
+                                   uint32_t pattern, uint32_t pair_bits) {
+  atomicAdd(&h_main[lut[pattern]], 1ull);
+  if (h_sub) {
+    const uint8_t g = lut[pattern & pair_bits];
+    if (g != 0xFF) atomicAdd(&h_sub[g], 1ull);
+  }
+}
+
+// Hash-set version.  Generator instances: every pairwise neighbour v of a, b
+// or c (witness 0, 1, 2), and every 3-node hyperedge f sharing exactly two
+// nodes with e, reached from the row of the smaller shared node (witness 3
+// for {a,b}, 4 for {a,c}, 5 for {b,c}).  An instance counts only when no
+// witness ahead of its own exists, so each v is taken once.
+template <bool OWN>
+__device__ void b4_edge_hash(uint32_t a, uint32_t b, uint32_t c, const uint32_t* __restrict__ e3,
+                             const uint32_t* __restrict__ g2_off, const uint32_t* __restrict__ g2_adj,
+                             const uint32_t* __restrict__ i3_off, const uint32_t* __restrict__ i3_idx,
+                             const Set64& hs2, const Set128& hs3, const Set128& hs4, const uint8_t* lut,
+                             unsigned long long* h_main, unsigned long long* h_sub) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const uint32_t pab = has2(hs2, a, b), pac = has2(hs2, a, c), pbc = has2(hs2, b, c);
+  const uint32_t base_p = pab | (pac << 1) | (pbc << 2) | (1u << 3);
+  uint32_t sb[5], sl[5];
+  sb[0] = g2_off[a]; sl[0] = g2_off[a + 1] - sb[0];
+  sb[1] = g2_off[b]; sl[1] = g2_off[b + 1] - sb[1];
+  sb[2] = g2_off[c]; sl[2] = g2_off[c + 1] - sb[2];
+  sb[3] = i3_off[a]; sl[3] = i3_off[a + 1] - sb[3];
+  sb[4] = i3_off[b]; sl[4] = i3_off[b + 1] - sb[4];
+  const uint32_t total = sl[0] + sl[1] + sl[2] + sl[3] + sl[4];
+  for (uint32_t t = lane; t < total; t += kWave) {
+    uint32_t seg = 0, off = t;
+    while (off >= sl[seg]) { off -= sl[seg]; ++seg; }
+    uint32_t v, src;
+    if (seg < 3) {
+      v = g2_adj[sb[seg] + off];
+      if (v == a || v == b || v == c) continue;
+      src = seg;
+    } else {
+      const uint32_t f = i3_idx[sb[seg] + off];
+      const uint32_t x = e3[3ull * f], y = e3[3ull * f + 1], z = e3[3ull * f + 2];
+      const bool xa = (x == a || x == b || x == c), ya = (y == a || y == b || y == c), za = (z == a || z == b || z == c);
+      if (int(xa) + int(ya) + int(za) != 2) continue;
+      v = !xa ? x : (!ya ? y : z);
+      const bool hasa = (x == a || y == a || z == a), hasb = (x == b || y == b || z == b);
+      if (seg == 3) {
+        src = hasb ? 3 : 4;          // {a,b,v} or {a,c,v}
+      } else {
+        if (hasa) continue;          // {a,b,v} is taken from a's row
+        src = 5;                     // {b,c,v}
+      }
+    }
+    // fill-in, cheapest witnesses first
+    const uint32_t qa = has2(hs2, a, v);
+    if (src > 0 && qa) continue;
+    const uint32_t qb = has2(hs2, b, v);
+    if (src > 1 && qb) continue;
+    const uint32_t qc = has2(hs2, c, v);
+    if (src > 2 && qc) continue;
+    uint32_t x0 = a, x1 = b, x2 = v;
+    sort3(x0, x1, x2);
+    const uint32_t tab = set128_has(hs3, key3(x0, x1, x2));
+    if (src > 3 && tab) continue;
+    if (OWN && tab && v < c) continue;                       // {a,b,v} precedes e
+    uint32_t y0 = a, y1 = c, y2 = v;
+    sort3(y0, y1, y2);
+    const uint32_t tac = set128_has(hs3, key3(y0, y1, y2));
+    if (src > 4 && tac) continue;
+    if (OWN && tac && v < b) continue;                       // {a,c,v} precedes e
+    uint32_t z0 = b, z1 = c, z2 = v;
+    sort3(z0, z1, z2);
+    const uint32_t tbc = set128_has(hs3, key3(z0, z1, z2));
+    if (OWN && tbc && v < a) continue;                       // {b,c,v} precedes e
+    uint32_t w0 = a, w1 = b, w2 = c, w3 = v;
+    if (w3 < w2) { w3 = w2; w2 = v; if (w2 < w1) { w2 = w1; w1 = v; if (w1 < w0) { w1 = w0; w0 = v; } } }
+    if (set128_has(hs4, key4(w0, w1, w2, w3))) continue;   // a 4-node hyperedge
+    // local positions a=0, b=1, c=2, v=3
+    const uint32_t p = base_p | (qa << 4) | (qb << 5) | (tab << 6) | (qc << 7) | (tac << 8) | (tbc << 9);
+    count_class(lut, h_main, h_sub, p, kPairBits4);
+  }
+}
+
+// Bit-row version.  The wavefront builds, in LDS, bit sets of the nodes v for
+// which {a,b,v}, {a,c,v}, {b,c,v} are 3-node hyperedges (from the incident
+// 3-node hyperedges of a and b) and for which e u {v} is a 4-node hyperedge
+// (from the incident 4-node hyperedges of a).  The candidates are the union of
+// these with the pairwise neighbours of a, b and c, compacted with popcount
+// prefix sums; fill-in of e u {v} is then a set of bit tests.
+template <bool OWN>
+__device__ void b4_edge_bits(uint32_t a, uint32_t b, uint32_t c, const uint32_t* __restrict__ e3,
+                             const uint32_t* __restrict__ e4, const uint32_t* __restrict__ i3_off,
+                             const uint32_t* __restrict__ i3_idx, const uint32_t* __restrict__ i4_off,
+                             const uint32_t* __restrict__ i4_idx, const uint32_t* __restrict__ bits, uint32_t W,
+                             B4Scratch& sc, const uint8_t* lut, unsigned long long* h_main,
+                             unsigned long long* h_sub) {
+  const int lane = threadIdx.x & (kWave - 1);
+  uint32_t* Tab = sc.sets[0];
+  uint32_t* Tac = sc.sets[1];
+  uint32_t* Tbc = sc.sets[2];
+  uint32_t* Q = sc.sets[3];
+  uint32_t* list = sc.list;
+  const uint32_t* Ra = bits + uint64_t(a) * W;
+  const uint32_t* Rb = bits + uint64_t(b) * W;
+  const uint32_t* Rc = bits + uint64_t(c) * W;
+  for (uint32_t w = lane; w < W; w += kWave) {
+    Tab[w] = 0; Tac[w] = 0; Tbc[w] = 0; Q[w] = 0;
+  }
+  wave_sync();
+  // 3-node hyperedges sharing two nodes with e
+  const uint32_t pa = i3_off[a], la = i3_off[a + 1] - pa;
+  const uint32_t pb = i3_off[b], lb = i3_off[b + 1] - pb;
+  for (uint32_t t = lane; t < la + lb; t += kWave) {
+    const uint32_t f = i3_idx[t < la ? pa + t : pb + (t - la)];
+    const uint32_t x = e3[3ull * f], y = e3[3ull * f + 1], z = e3[3ull * f + 2];
+    const bool ha = (x == a || y == a || z == a), hb = (x == b || y == b || z == b), hc = (x == c || y == c || z == c);
+    if (int(ha) + int(hb) + int(hc) != 2) continue;
+    const uint32_t v = (x != a && x != b && x != c) ? x : ((y != a && y != b && y != c) ? y : z);
+    uint32_t* T = (ha && hb) ? Tab : (ha ? Tac : Tbc);
+    atomicOr(&T[v >> 5], 1u << (v & 31));
+  }
+  // 4-node hyperedges containing e
+  const uint32_t p4 = i4_off[a], l4 = i4_off[a + 1] - p4;
+  for (uint32_t t = lane; t < l4; t += kWave) {
+    const uint32_t f = i4_idx[p4 + t];
+    const uint32_t m[4] = {e4[4ull * f], e4[4ull * f + 1], e4[4ull * f + 2], e4[4ull * f + 3]};
+    int hits = 0;
+    uint32_t v = 0;
+    for (int j = 0; j < 4; ++j) {
+      if (m[j] == a || m[j] == b || m[j] == c) ++hits; else v = m[j];
+    }
+    if (hits == 3) atomicOr(&Q[v >> 5], 1u << (v & 31));
+  }
+  wave_sync();
+  const uint32_t pab = (Ra[b >> 5] >> (b & 31)) & 1u, pac = (Ra[c >> 5] >> (c & 31)) & 1u,
+                 pbc = (Rb[c >> 5] >> (c & 31)) & 1u;
+  const uint32_t base_p = pab | (pac << 1) | (pbc << 2) | (1u << 3);
+  for (uint32_t w0 = 0; w0 < W; w0 += kChunkWords) {
+    const uint32_t w = w0 + lane;
+    uint32_t cw = 0;
+    if (w < W) {
+      cw = Ra[w] | Rb[w] | Rc[w] | Tab[w] | Tac[w] | Tbc[w];
+      if ((a >> 5) == w) cw &= ~(1u << (a & 31));
+      if ((b >> 5) == w) cw &= ~(1u << (b & 31));
+      if ((c >> 5) == w) cw &= ~(1u << (c & 31));
+    }
+    uint32_t total;
+    uint32_t pos = wave_exclusive_scan(__popc(cw), &total);
+    while (cw) {
+      const uint32_t bit = __ffs(cw) - 1;
+      cw &= cw - 1;
+      list[pos++] = (w << 5) | bit;
+    }
+    wave_sync();
+    for (uint32_t t = lane; t < total; t += kWave) {
+      const uint32_t v = list[t];
+      const uint32_t vw = v >> 5, vb = v & 31;
+      if ((Q[vw] >> vb) & 1u) continue;                    // a 4-node hyperedge
+      const uint32_t tab = (Tab[vw] >> vb) & 1u, tac = (Tac[vw] >> vb) & 1u, tbc = (Tbc[vw] >> vb) & 1u;
+      if (OWN && ((tab && v < c) || (tac && v < b) || (tbc && v < a))) continue;   // an earlier 3-node hyperedge
+      const uint32_t qa = (Ra[vw] >> vb) & 1u, qb = (Rb[vw] >> vb) & 1u, qc = (Rc[vw] >> vb) & 1u;
+      // local positions a=0, b=1, c=2, v=3
+      const uint32_t pt = base_p | (qa << 4) | (qb << 5) | (tab << 6) | (qc << 7) | (tac << 8) | (tbc << 9);
+      count_class(lut, h_main, h_sub, pt, kPairBits4);
+    }
+    wave_sync();
+  }
+}
+
+}  // namespace hm

@@ -1,0 +1,136 @@
+// Device helpers shared by the counting kernels: pair/triple existence
+// tests (fill-in, Section 4.3 Fig. 3b), bit-row masks, wavefront scans and
+// reductions, LDS class-counter helpers and the Philox4x64-10 generator.
+#pragma once
+
+#include "hm_internal.h"
+
+namespace hm {
+
+constexpr int kThreads = 256;
+constexpr int kWavesPerBlock = kThreads / kWave;
+// pattern bits of the pairs among 4 local nodes: masks 3,5,6,9,10,12 -> bits 0,1,2,4,5,7
+constexpr uint32_t kPairBits4 = (1u << 0) | (1u << 1) | (1u << 2) | (1u << 4) | (1u << 5) | (1u << 7);
+constexpr uint32_t kPairBits3 = 0x7u;
+
+__device__ inline bool has2(const Set64& s, uint32_t u, uint32_t v) {
+  return set64_has(s, u < v ? key2(u, v) : key2(v, u));
+}
+__device__ inline void sort3(uint32_t& a, uint32_t& b, uint32_t& c) {
+  uint32_t t;
+  if (a > b) { t = a; a = b; b = t; }
+  if (b > c) { t = b; b = c; c = t; }
+  if (a > b) { t = a; a = b; b = t; }
+}
+__device__ inline bool has3(const Set128& s, uint32_t a, uint32_t b, uint32_t c) {
+  sort3(a, b, c);
+  return set128_has(s, key3(a, b, c));
+}
+// lexicographic comparison of ascending triples
+__device__ inline bool tri_less(uint32_t a0, uint32_t a1, uint32_t a2, uint32_t b0, uint32_t b1, uint32_t b2) {
+  if (a0 != b0) return a0 < b0;
+  if (a1 != b1) return a1 < b1;
+  return a2 < b2;
+}
+__device__ inline bool bit_of(const uint32_t* bits, uint32_t words, uint32_t u, uint32_t v) {
+  return (bits[uint64_t(u) * words + (v >> 5)] >> (v & 31)) & 1u;
+}
+// bits of word w whose node index is greater than y
+__device__ inline uint32_t mask_gt(uint32_t y, uint32_t w) {
+  const uint32_t lo = w << 5;
+  if (y < lo) return ~0u;
+  const uint32_t d = y - lo;
+  if (d >= 31) return 0u;
+  return ~0u << (d + 1);
+}
+// bits of word w whose node index is below n
+__device__ inline uint32_t mask_below(uint32_t n, uint32_t w) {
+  const uint32_t lo = w << 5;
+  if (lo + 32 <= n) return ~0u;
+  if (lo >= n) return 0u;
+  return (1u << (n - lo)) - 1u;
+}
+// first position in the ascending row [p, e) whose value is greater than x
+__device__ inline uint32_t upper_bound(const uint32_t* adj, uint32_t p, uint32_t e, uint32_t x) {
+  while (p < e) {
+    uint32_t m = p + ((e - p) >> 1);
+    if (adj[m] <= x) p = m + 1; else e = m;
+  }
+  return p;
+}
+__device__ inline unsigned long long wave_sum(unsigned long long v) {
+  uint32_t lo = uint32_t(v), hi = uint32_t(v >> 32);
+#pragma unroll
+  for (int d = kWave / 2; d > 0; d >>= 1) {
+    uint32_t olo = __shfl_xor(lo, d, kWave);
+    uint32_t ohi = __shfl_xor(hi, d, kWave);
+    unsigned long long s = ((unsigned long long)hi << 32 | lo) + ((unsigned long long)ohi << 32 | olo);
+    lo = uint32_t(s);
+    hi = uint32_t(s >> 32);
+  }
+  return (unsigned long long)hi << 32 | lo;
+}
+
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+__device__ inline uint32_t wave_exclusive_scan(uint32_t v, uint32_t* total) {
+  const int lane = threadIdx.x & (kWave - 1);
+  uint32_t x = v;
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    const uint32_t y = __shfl_up(x, d, kWave);
+    if (lane >= d) x += y;
+  }
+  *total = __shfl(x, kWave - 1, kWave);
+  return x - v;
+}
+
+__device__ inline void load_lut(uint8_t* lut, const uint8_t* g, int n) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) lut[i] = g[i];
+}
+
+__device__ inline void flush(unsigned long long* lds, unsigned long long* out, int n) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x)
+    if (lds[i]) atomicAdd(out + i, lds[i]);
+}
+
+__device__ inline uint32_t pair_bit(const Set64& hs2, const uint32_t* bits, uint32_t W, uint32_t u, uint32_t v) {
+  return bits ? ((bits[uint64_t(u) * W + (v >> 5)] >> (v & 31)) & 1u) : uint32_t(has2(hs2, u, v));
+}
+
+
+// Philox4x64-10 (Salmon et al., SC'11): ten rounds of two 64x64->128-bit
+// multiplications with the round keys bumped by the Weyl constants.
+struct Philox4 {
+  unsigned long long v[4];
+};
+__device__ inline Philox4 philox4x64_10(unsigned long long c0, unsigned long long c1, unsigned long long c2,
+                                        unsigned long long c3, unsigned long long k0, unsigned long long k1) {
+  const unsigned long long M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+  const unsigned long long W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const unsigned long long hi0 = __umul64hi(M0, c0), lo0 = M0 * c0;
+    const unsigned long long hi1 = __umul64hi(M1, c2), lo1 = M1 * c2;
+    const unsigned long long n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+    c0 = n0;
+    c1 = lo1;
+    c2 = n2;
+    c3 = lo0;
+    k0 += W0;
+    k1 += W1;
+  }
+  return Philox4{{c0, c1, c2, c3}};
+}
+// a value in [0, n) from a uniform 64-bit word: the high word of word * n
+__device__ inline unsigned long long bounded64(unsigned long long word, unsigned long long n) {
+  return __umul64hi(word, n);
+}
+constexpr unsigned long long kDomainSample = 1ull;
+constexpr unsigned long long kDomainNull = 2ull;
+constexpr unsigned long long kDomainProposal = 3ull;
+
+}  // namespace hm

@@ -202,4 +202,7 @@ struct hm_graph {
 
   // histogram scratch, reused by the counting calls (serialised per graph)
   unsigned long long* hist = nullptr;      // 4 x 256 counters
+  // sample index scratch of the sampled counting calls
+  uint32_t* sample_idx = nullptr;
+  uint64_t sample_cap = 0;
 };

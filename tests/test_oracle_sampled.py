@@ -158,3 +158,12 @@ def test_mre_definition():
     exact = np.array([100.0, 0.0, 50.0])
     runs = np.array([[110.0, 0.0, 40.0], [90.0, 3.0, 50.0]])
     assert stats.mean_relative_error(runs, exact) == pytest.approx(((10 + 10) / 150 + (10 + 3) / 150) / 2)
+
+
+def test_sample_sizes_rule():
+    n = {2: 12258, 3: 11313, 4: 4549}
+    assert core.sample_sizes(n, 4, 0.01) == {2: 123, 3: 114, 4: 46}
+    s = 28120 // 100 + 1                           # ceil(0.01 * 28120) = 282
+    assert core.sample_sizes(n, 4, 0.01, core.ALLOC_PAPER) == {2: s // 6, 3: s // 2, 4: s - s // 6 - s // 2}
+    assert core.sample_sizes({2: 10, 3: 0}, 3, 0.5) == {2: 5, 3: 0}
+    assert core.sample_sizes(n, 3, 1.0, core.ALLOC_PAPER) == {2: 12258, 3: 11313}
