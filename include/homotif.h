@@ -101,10 +101,10 @@ int hm_graph_create(const uint32_t* members, const uint64_t* offsets, uint64_t n
 /* Release a graph handle (NULL is accepted). */
 int hm_graph_destroy(hm_graph* H);
 
-/* Host array of 8 values: n_nodes, unique hyperedges of size 2, 3, 4, unique
+/* Host array of 10 values: n_nodes, unique hyperedges of size 2, 3, 4, unique
  * hyperedges of size >= 5, input hyperedges, dropped singletons, collapsed
- * repeats. */
-int hm_graph_stats(const hm_graph* H, uint64_t* out8);
+ * repeats, unique hyperedges of size >= 2, their total number of members. */
+int hm_graph_stats(const hm_graph* H, uint64_t* out10);
 
 /* Copy the unique hyperedges of size j (2..4), stratum order, as ascending
  * j-tuples into the host buffer `out` (|E_j| * j values). */
@@ -160,6 +160,37 @@ int count_sampled(const hm_graph* H, int k, double fraction, uint64_t seed, int 
  * (checked before counting; this call synchronises the stream once). */
 int count_sampled_indices(const hm_graph* H, int k, const uint32_t* idx2, uint64_t s2, const uint32_t* idx3,
                           uint64_t s3, const uint32_t* idx4, uint64_t s4, float* est, int64_t* raw, void* stream);
+
+/* ---------------------------------------------------------------- nulls */
+
+/* Motif over/under-expression against randomised hypergraphs (Section 1:
+ * count, count again on randomisations, score; Section 6.3 uses a
+ * configuration model).  The null model is stub matching that keeps every
+ * node degree and every hyperedge size: the stubs are the members (ascending)
+ * of the unique hyperedges of size >= 2 in stratum order; copy c uses the
+ * Philox4x64-10 key (seed, (2 << 32) | c); round 0 orders the stubs by
+ * (word0 of counter (t, 0, 0, 0), t) and cuts them into the size sequence;
+ * while a hyperedge repeats a node (rounds r = 1..64), the offending
+ * hyperedges B (ascending) each take a partner hi64(word0 of counter
+ * (q, r, 1, 0) * E), and the members of B u partners are reordered by
+ * (word0 of counter (t, r, 0, 0), t) and dealt back in ascending hyperedge
+ * order.  Each copy is counted exactly (repeated hyperedges collapse) and
+ * z_m = (real_m - mean_m) / sd_m (sd over the copies with n_rand - 1; fp64,
+ * rounded to fp32; +-inf when sd = 0 and real differs from the mean, 0 when
+ * it does not).
+ *   real   device int64[C] exact counts of H, or NULL
+ *   nulls  device int64[n_rand * C], copy-major (required)
+ *   z      device float[C], or NULL
+ * n_rand in [2, 65535]; HM_EINVAL when a copy cannot be repaired.
+ * Synchronises `stream` before returning. */
+int count_nulls(const hm_graph* H, int k, int n_rand, uint64_t seed, int64_t* real, int64_t* nulls, float* z,
+                void* stream);
+
+/* Null copy `copy` of count_nulls' model (host outputs): members in the
+ * copy's stored order (offsets[n_unique] values) and the offsets of the size
+ * sequence (n_unique + 1 values, n_unique = unique hyperedges of size >= 2).
+ * Synchronous. */
+int hm_null_export(const hm_graph* H, uint64_t seed, uint32_t copy, uint32_t* members, uint64_t* offsets);
 
 /* ---------------------------------------------------------------- options */
 

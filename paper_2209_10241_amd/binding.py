@@ -65,6 +65,8 @@ SIGNATURES = {
     "hm_sample_draw": (_int, [_vp, _int, _dbl, _u64, _int, _vp, _vp, _vp, _vp]),
     "count_sampled": (_int, [_vp, _int, _dbl, _u64, _int, _vp, _vp, _vp]),
     "count_sampled_indices": (_int, [_vp, _int, _vp, _u64, _vp, _u64, _vp, _u64, _vp, _vp, _vp]),
+    "count_nulls": (_int, [_vp, _int, _int, _u64, _vp, _vp, _vp, _vp]),
+    "hm_null_export": (_int, [_vp, _u64, _u32, _vp, _vp]),
     "hm_set_option": (_int, [_int, ctypes.c_int64]),
     "hm_get_option": (_int, [_int, _vp]),
     "hm_profile_enable": (_int, [_int]),
@@ -137,9 +139,10 @@ class Graph:
         return self._h
 
     def stats(self) -> dict:
-        out = (ctypes.c_uint64 * 8)()
+        out = (ctypes.c_uint64 * 10)()
         _check(lib().hm_graph_stats(self.handle, out))
-        keys = ["n_nodes", "n2", "n3", "n4", "n5plus", "n_input", "singletons", "duplicates"]
+        keys = ["n_nodes", "n2", "n3", "n4", "n5plus", "n_input", "singletons", "duplicates", "n_unique",
+                "n_unique_members"]
         return dict(zip(keys, [int(x) for x in out]))
 
     def export(self, j: int) -> np.ndarray:
@@ -299,3 +302,25 @@ def count_sampled_indices(H: Graph, k: int, samples: dict, est=None, raw=None, s
                                        size[4], ctypes.c_void_p(est.data_ptr()), ctypes.c_void_p(raw.data_ptr()),
                                        _stream_ptr(stream)))
     return est, raw
+
+
+def count_nulls(H: Graph, k: int, n_rand: int, seed: int, stream=None):
+    """(real int64[C], nulls int64[n_rand, C], z fp32[C]) torch tensors on the current device."""
+    import torch
+    n = hm_num_classes(k)
+    real = torch.empty(n, dtype=torch.int64, device="cuda")
+    nulls = torch.empty((n_rand, n), dtype=torch.int64, device="cuda")
+    z = torch.empty(n, dtype=torch.float32, device="cuda")
+    _check(lib().count_nulls(H.handle, k, n_rand, int(seed) & (2**64 - 1), ctypes.c_void_p(real.data_ptr()),
+                             ctypes.c_void_p(nulls.data_ptr()), ctypes.c_void_p(z.data_ptr()), _stream_ptr(stream)))
+    return real, nulls, z
+
+
+def hm_null_export(H: Graph, seed: int, copy: int):
+    """(members uint32, offsets uint64) numpy arrays of one null copy."""
+    st = H.stats()
+    members = np.zeros(max(1, st["n_unique_members"]), dtype=np.uint32)
+    offsets = np.zeros(st["n_unique"] + 1, dtype=np.uint64)
+    _check(lib().hm_null_export(H.handle, int(seed) & (2**64 - 1), copy, members.ctypes.data_as(ctypes.c_void_p),
+                                offsets.ctypes.data_as(ctypes.c_void_p)))
+    return members[:st["n_unique_members"]], offsets

@@ -596,7 +596,8 @@ int hm_graph_destroy(hm_graph* H) {
   return HM_OK;
 }
 
-int hm_graph_stats(const hm_graph* H, uint64_t* out8) {
+int hm_graph_stats(const hm_graph* H, uint64_t* out10) {
+  uint64_t* out8 = out10;
   if (!H || !out8) {
     hm::set_error("NULL argument");
     return HM_EINVAL;
@@ -609,6 +610,8 @@ int hm_graph_stats(const hm_graph* H, uint64_t* out8) {
   out8[5] = H->n_input;
   out8[6] = H->n_singletons;
   out8[7] = H->n_duplicates;
+  out8[8] = H->n_unique;
+  out8[9] = H->n_unique_members;
   return HM_OK;
 }
 
