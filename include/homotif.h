@@ -182,9 +182,19 @@ int count_sampled_indices(const hm_graph* H, int k, const uint32_t* idx2, uint64
  *   nulls  device int64[n_rand * C], copy-major (required)
  *   z      device float[C], or NULL
  * n_rand in [2, 65535]; HM_EINVAL when a copy cannot be repaired.
- * Synchronises `stream` before returning. */
+ * All copies are generated, ingested and counted together: batched kernels
+ * over (copy, hyperedge) index spaces and one persistent counting kernel that
+ * takes (phase, copy, chunk) tiles from a device queue.  The first call for a
+ * (graph, k, n_rand) allocates the buffers, picks the tile sizes by timing
+ * (cached per device and shape for the process) and captures the pipeline in
+ * a HIP graph; every call replays that graph (the seed is read from device
+ * memory).  Synchronises `stream` before returning. */
 int count_nulls(const hm_graph* H, int k, int n_rand, uint64_t seed, int64_t* real, int64_t* nulls, float* z,
                 void* stream);
+
+/* Items per tile chosen for the last count_nulls on H (host array of 3:
+ * 3-node hyperedges, pairs, hyperedges of size k); HM_EINVAL before any. */
+int hm_null_tile_sizes(const hm_graph* H, uint32_t* out3);
 
 /* Null copy `copy` of count_nulls' model (host outputs): members in the
  * copy's stored order (offsets[n_unique] values) and the offsets of the size

@@ -67,6 +67,7 @@ SIGNATURES = {
     "count_sampled_indices": (_int, [_vp, _int, _vp, _u64, _vp, _u64, _vp, _u64, _vp, _vp, _vp]),
     "count_nulls": (_int, [_vp, _int, _int, _u64, _vp, _vp, _vp, _vp]),
     "hm_null_export": (_int, [_vp, _u64, _u32, _vp, _vp]),
+    "hm_null_tile_sizes": (_int, [_vp, _vp]),
     "hm_set_option": (_int, [_int, ctypes.c_int64]),
     "hm_get_option": (_int, [_int, _vp]),
     "hm_profile_enable": (_int, [_int]),
@@ -324,3 +325,9 @@ def hm_null_export(H: Graph, seed: int, copy: int):
     _check(lib().hm_null_export(H.handle, int(seed) & (2**64 - 1), copy, members.ctypes.data_as(ctypes.c_void_p),
                                 offsets.ctypes.data_as(ctypes.c_void_p)))
     return members[:st["n_unique_members"]], offsets
+
+
+def hm_null_tile_sizes(H: Graph):
+    out = (ctypes.c_uint32 * 3)()
+    _check(lib().hm_null_tile_sizes(H.handle, out))
+    return [int(x) for x in out]

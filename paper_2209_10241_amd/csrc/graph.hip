@@ -534,6 +534,8 @@ void release(hm_graph* H) {
   dfree(H->bits);
   dfree(H->hist);
   dfree(H->sample_idx);
+  if (H->null_plan) destroy_null_plan(H->null_plan);
+  H->null_plan = nullptr;
 }
 
 }  // namespace

@@ -137,12 +137,26 @@ int scan_exclusive_u64(const unsigned long long* in, unsigned long long* out, ui
 int radix_sort_pairs(unsigned long long* keys, uint32_t* vals, unsigned long long* keys_tmp,
                      uint32_t* vals_tmp, uint64_t n, int bits, hipStream_t stream);
 int fill_u32(uint32_t* p, uint32_t value, uint64_t n, hipStream_t stream);
+int copy_u32(const uint32_t* src, uint32_t* dst, uint64_t n, hipStream_t stream);
+int copy_u64(const unsigned long long* src, unsigned long long* dst, uint64_t n, hipStream_t stream);
+// Workspace variants: no allocation, no host synchronisation (usable under
+// stream capture).  The workspace sizes are in uint32 words.
+uint64_t scan_ws_words(uint64_t n);
+int scan_u32_ws(const uint32_t* in, uint32_t* out, uint64_t n, uint32_t* total_dev, uint32_t* ws,
+                hipStream_t stream);
+uint64_t radix_ws_words(uint64_t n);
+int radix_sort_ws(unsigned long long* keys, uint32_t* vals, unsigned long long* keys_tmp, uint32_t* vals_tmp,
+                  uint64_t n, int bits, uint32_t* ws, hipStream_t stream);
 int fill_u64(unsigned long long* p, unsigned long long value, uint64_t n, hipStream_t stream);
 
 // ----------------------------------------------------------------- profiling
 // While hm_profile_enable(1) is in effect, a scope records HIP events around
 // the launches it encloses on `st`, under `name`.
 bool profiling();
+// Kernel launches enqueued between capture_begin and capture_end go into a
+// HIP graph; profiling scopes stay inactive meanwhile.
+void capture_begin();
+void capture_end();
 class ProfileScope {
  public:
   ProfileScope(const char* name, hipStream_t st);
@@ -160,6 +174,9 @@ class ProfileScope {
 // ----------------------------------------------------------------- device allocations
 int dalloc(void** p, size_t bytes);
 void dfree(void* p);
+
+struct NullPlan;
+void destroy_null_plan(NullPlan* p);
 
 }  // namespace hm
 
@@ -205,4 +222,6 @@ struct hm_graph {
   // sample index scratch of the sampled counting calls
   uint32_t* sample_idx = nullptr;
   uint64_t sample_cap = 0;
+  // buffers and captured HIP graph of the batched null-model pipeline
+  hm::NullPlan* null_plan = nullptr;
 };

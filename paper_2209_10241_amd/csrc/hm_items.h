@@ -1,0 +1,333 @@
+// Per-item bodies of the exact counting kernels, shared by the one-graph
+// kernels (exact.hip) and the persistent batched kernel of the null model
+// (nulls_batch.hip).  A View holds the device structures of one hypergraph
+// (or of one null copy); incidence indices are positions in e3 / e4.
+//
+// Order 4 (Algorithm 3, Section 4.2), with the "visited" set replaced by
+// ownership rules decided from the node set alone:
+//   (a) a 4-node hyperedge counts its own node set;
+//   (b) a set that is not a 4-node hyperedge but holds a 3-node hyperedge is
+//       counted by its smallest 3-node hyperedge (hm_b4.h);
+//   (c) a set whose sub-hypergraph holds only pairs is a connected 4-node set
+//       of the pairwise graph G2 that (a) and (b) did not count: the pairwise
+//       graph's connected 4-node sets are counted per induced shape (each set
+//       from its smallest node r), and the shapes of the G2-connected sets
+//       counted by (a) and (b) are subtracted.
+// Order 3 (Algorithm 2): (a) each 3-node hyperedge, (c) wedges and triangles
+// of G2 minus those that are 3-node hyperedges.
+#pragma once
+
+#include "hm_b4.h"
+
+namespace hm {
+
+struct View {
+  const uint32_t* e2;       // pairs (r < x) of this graph
+  const uint32_t* e3;       // 3-node hyperedges (positions referenced by i3_idx)
+  const uint32_t* e4;       // 4-node hyperedges (positions referenced by i4_idx)
+  const uint32_t* g2_off;   // n_nodes + 1 absolute row starts in g2_adj
+  const uint32_t* g2_adj;   // ascending neighbour rows
+  const uint32_t* i3_off;
+  const uint32_t* i3_idx;
+  const uint32_t* i4_off;
+  const uint32_t* i4_idx;
+  Set64 hs2;
+  Set128 hs3, hs4;
+  const uint32_t* bits;     // n_nodes x W words, or null
+  uint32_t W;
+  uint32_t N;
+};
+
+inline View view_of(const hm_graph* H) {
+  View v;
+  v.e2 = H->e2;
+  v.e3 = H->e3;
+  v.e4 = H->e4;
+  v.g2_off = H->g2_off;
+  v.g2_adj = H->g2_adj;
+  v.i3_off = H->i3_off;
+  v.i3_idx = H->i3_idx;
+  v.i4_off = H->i4_off;
+  v.i4_idx = H->i4_idx;
+  v.hs2 = H->hs2;
+  v.hs3 = H->hs3;
+  v.hs4 = H->hs4;
+  v.bits = H->bits;
+  v.W = H->words;
+  v.N = H->n_nodes;
+  return v;
+}
+
+// histogram regions (256 counters each)
+constexpr int kMain = 0;    // classes counted by (a) and (b)
+constexpr int kSub = 256;   // G2 shape of G2-connected sets counted by (a) and (b)
+constexpr int kG2 = 512;    // G2 shape counts of all connected sets of G2
+constexpr int kHistWords = 768;
+
+// (a) at order 4: the pattern of a 4-node hyperedge; local positions a..d = 0..3
+__device__ inline uint32_t a4_pattern(const View& v, uint32_t a, uint32_t b, uint32_t c, uint32_t d) {
+  uint32_t p = 1u << 10;
+  p |= pair_bit(v.hs2, v.bits, v.W, a, b) << 0;
+  p |= pair_bit(v.hs2, v.bits, v.W, a, c) << 1;
+  p |= pair_bit(v.hs2, v.bits, v.W, b, c) << 2;
+  p |= uint32_t(set128_has(v.hs3, key3(a, b, c))) << 3;
+  p |= pair_bit(v.hs2, v.bits, v.W, a, d) << 4;
+  p |= pair_bit(v.hs2, v.bits, v.W, b, d) << 5;
+  p |= uint32_t(set128_has(v.hs3, key3(a, b, d))) << 6;
+  p |= pair_bit(v.hs2, v.bits, v.W, c, d) << 7;
+  p |= uint32_t(set128_has(v.hs3, key3(a, c, d))) << 8;
+  p |= uint32_t(set128_has(v.hs3, key3(b, c, d))) << 9;
+  return p;
+}
+
+// (a) at order 3: the pattern of a 3-node hyperedge; local positions a,b,c = 0,1,2
+__device__ inline uint32_t a3_pattern(const View& v, uint32_t a, uint32_t b, uint32_t c) {
+  return (1u << 3) | pair_bit(v.hs2, v.bits, v.W, a, b) | (pair_bit(v.hs2, v.bits, v.W, a, c) << 1) |
+         (pair_bit(v.hs2, v.bits, v.W, b, c) << 2);
+}
+
+// (b) at order 4 for the 3-node hyperedge at position i of v.e3
+__device__ inline void b4_item(const View& v, uint64_t i, B4Scratch* sc, const uint8_t* lut, unsigned long long* h_main,
+                               unsigned long long* h_sub) {
+  const uint32_t a = v.e3[3 * i], b = v.e3[3 * i + 1], c = v.e3[3 * i + 2];
+  if (v.bits)
+    b4_edge_bits<true>(a, b, c, v.e3, v.e4, v.i3_off, v.i3_idx, v.i4_off, v.i4_idx, v.bits, v.W, *sc, lut, h_main,
+                       h_sub);
+  else
+    b4_edge_hash<true>(a, b, c, v.e3, v.g2_off, v.g2_adj, v.i3_off, v.i3_idx, v.hs2, v.hs3, v.hs4, lut, h_main, h_sub);
+}
+
+// ---------------------------------------------------------------- (c), order 4, bit rows
+// One wavefront per pair {r < x}.  Shapes with A = N(r) n V':
+//   |A| = 3: {r,x,y,z}, x<y<z all neighbours of r
+//   |A| = 2: x<y neighbours of r, z > r not a neighbour of r, adjacent to x or y
+//   |A| = 1: x the only neighbour of r; y,z > r non-neighbours of r with
+//            {x,y,z} connected: y<z both adjacent to x, or y~x, z~y, z!~x.
+// A row has W words.  With W <= 64 the wavefront is split into 64/W groups of
+// W lanes, lane (g, w) owning word w of every y its group takes, so the words
+// of r and x and the masks that depend only on r are loaded once per pair;
+// wider rows loop over words.  Each word adds popcounts of the candidate z it
+// holds, split by the adjacency of z to x and y.
+// Named scalars (no arrays) keep every counter in registers.
+struct C4Acc {
+  // |A| = 3, by (x~y, x~z, y~z)
+  unsigned long long a000, a001, a010, a011, a100, a101, a110, a111;
+  // |A| = 2, by x~y and z adjacent to both / x only / y only
+  unsigned long long b0b, b0x, b0y, b1b, b1x, b1y;
+  // |A| = 1
+  unsigned long long paw, star, path;
+};
+
+struct C4Lanes {
+  uint32_t G, g, w0, wstep;
+  bool on;
+};
+
+__device__ inline C4Lanes c4_lanes(uint32_t W) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const bool grouped = W <= uint32_t(kWave);
+  C4Lanes L;
+  L.G = grouped ? uint32_t(kWave) / W : 1u;
+  L.g = grouped ? uint32_t(lane) / W : 0u;
+  L.w0 = grouped ? uint32_t(lane) % W : uint32_t(lane);
+  L.wstep = grouped ? W : uint32_t(kWave);
+  L.on = grouped ? (L.g < L.G) : true;
+  return L;
+}
+
+__device__ inline void c4_zero(C4Acc& a) {
+  a.a000 = a.a001 = a.a010 = a.a011 = a.a100 = a.a101 = a.a110 = a.a111 = 0;
+  a.b0b = a.b0x = a.b0y = a.b1b = a.b1x = a.b1y = 0;
+  a.paw = a.star = a.path = 0;
+}
+
+__device__ inline void c4_word(uint32_t Nr, uint32_t Nx, uint32_t Ny, uint32_t gy, uint32_t wr, bool xy, C4Acc& a) {
+  const uint32_t z3 = Nr & gy;
+  const uint32_t z3x = z3 & Nx, z3n = z3 & ~Nx;
+  const uint32_t c11 = __popc(z3x & Ny), c10 = __popc(z3x & ~Ny), c01 = __popc(z3n & Ny), c00 = __popc(z3n & ~Ny);
+  const uint32_t z2 = wr & (Nx | Ny);
+  const uint32_t b2 = __popc(z2 & Nx & Ny), bx = __popc(z2 & Nx & ~Ny), by = __popc(z2 & ~Nx & Ny);
+  const uint32_t m1 = xy ? ~0u : 0u, m0 = ~m1;
+  a.a011 += c11 & m0; a.a010 += c10 & m0; a.a001 += c01 & m0; a.a000 += c00 & m0;
+  a.a111 += c11 & m1; a.a110 += c10 & m1; a.a101 += c01 & m1; a.a100 += c00 & m1;
+  a.b0b += b2 & m0; a.b0x += bx & m0; a.b0y += by & m0;
+  a.b1b += b2 & m1; a.b1x += bx & m1; a.b1y += by & m1;
+}
+
+// ys: 64 words of wavefront-private LDS
+__device__ inline void c4_bits_item(const View& v, uint32_t r, uint32_t x, const C4Lanes& L, uint32_t* ys, C4Acc& acc) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const uint32_t W = v.W;
+  const uint32_t* Rr = v.bits + uint64_t(r) * W;
+  const uint32_t* Rx = v.bits + uint64_t(x) * W;
+  const uint32_t re = v.g2_off[r + 1];
+  const uint32_t p = upper_bound(v.g2_adj, v.g2_off[r], re, x);
+  const uint32_t xe = v.g2_off[x + 1];
+  const uint32_t q = upper_bound(v.g2_adj, v.g2_off[x], xe, r);
+  // |A| = 3 and |A| = 2: y over the neighbours of r above x, 64 at a time
+  for (uint32_t base = p; base < re; base += kWave) {
+    const uint32_t cnt = min(uint32_t(kWave), re - base);
+    if (uint32_t(lane) < cnt) ys[lane] = v.g2_adj[base + lane];
+    wave_sync();
+    if (L.on)
+      for (uint32_t w = L.w0; w < W; w += L.wstep) {
+        const uint32_t Nr = Rr[w], Nx = Rx[w];
+        const uint32_t wr = ~Nr & mask_gt(r, w) & mask_below(v.N, w);
+        for (uint32_t j = L.g; j < cnt; j += L.G) {
+          const uint32_t y = ys[j];
+          const uint32_t Ny = v.bits[uint64_t(y) * W + w];
+          const bool xy = (Rx[y >> 5] >> (y & 31)) & 1u;
+          c4_word(Nr, Nx, Ny, mask_gt(y, w), wr, xy, acc);
+        }
+      }
+    wave_sync();
+  }
+  // |A| = 1: y over the neighbours of x above r that are not neighbours of r
+  for (uint32_t base = q; base < xe; base += kWave) {
+    const bool in = base + lane < xe;
+    const uint32_t y0 = in ? v.g2_adj[base + lane] : 0u;
+    const bool keep = in && !((Rr[y0 >> 5] >> (y0 & 31)) & 1u);
+    const unsigned long long mk = __ballot(keep);
+    const uint32_t cnt = uint32_t(__popcll(mk));
+    if (keep) ys[__popcll(mk & ((1ull << lane) - 1ull))] = y0;
+    wave_sync();
+    if (L.on)
+      for (uint32_t w = L.w0; w < W; w += L.wstep) {
+        const uint32_t Nr = Rr[w], Nx = Rx[w];
+        const uint32_t wr = ~Nr & mask_gt(r, w) & mask_below(v.N, w);
+        const uint32_t nxw = Nx & wr;
+        for (uint32_t j = L.g; j < cnt; j += L.G) {
+          const uint32_t y = ys[j];
+          const uint32_t Ny = v.bits[uint64_t(y) * W + w];
+          const uint32_t zz = nxw & mask_gt(y, w);
+          acc.paw += __popc(zz & Ny);
+          acc.star += __popc(zz & ~Ny);
+          acc.path += __popc(Ny & wr & ~Nx);
+        }
+      }
+    wave_sync();
+  }
+}
+
+// Reduce the accumulators over the wavefront and add them to the G2-shape
+// counters h_g2 (lane 0 adds); every lane of the wavefront must call this.
+__device__ inline void c4_emit(unsigned long long value, uint32_t pattern, const uint8_t* lut,
+                               unsigned long long* h_g2) {
+  const unsigned long long sum = wave_sum(value);
+  if ((threadIdx.x & (kWave - 1)) == 0 && sum) atomicAdd(&h_g2[lut[pattern]], sum);
+}
+
+__device__ inline void c4_flush(const C4Acc& a, const uint8_t* lut, unsigned long long* h_g2) {
+  // local positions r=0, x=1, y=2, z=3; pair bits: rx 0, ry 1, xy 2, rz 4, xz 5, yz 7
+  constexpr uint32_t rx = 1u << 0, ry = 1u << 1, xy = 1u << 2, rz = 1u << 4, xz = 1u << 5, yz = 1u << 7;
+  c4_emit(a.a000, rx | ry | rz, lut, h_g2);
+  c4_emit(a.a001, rx | ry | rz | yz, lut, h_g2);
+  c4_emit(a.a010, rx | ry | rz | xz, lut, h_g2);
+  c4_emit(a.a011, rx | ry | rz | xz | yz, lut, h_g2);
+  c4_emit(a.a100, rx | ry | xy | rz, lut, h_g2);
+  c4_emit(a.a101, rx | ry | xy | rz | yz, lut, h_g2);
+  c4_emit(a.a110, rx | ry | xy | rz | xz, lut, h_g2);
+  c4_emit(a.a111, rx | ry | xy | rz | xz | yz, lut, h_g2);
+  c4_emit(a.b0b, rx | ry | xz | yz, lut, h_g2);
+  c4_emit(a.b0x, rx | ry | xz, lut, h_g2);
+  c4_emit(a.b0y, rx | ry | yz, lut, h_g2);
+  c4_emit(a.b1b, rx | ry | xy | xz | yz, lut, h_g2);
+  c4_emit(a.b1x, rx | ry | xy | xz, lut, h_g2);
+  c4_emit(a.b1y, rx | ry | xy | yz, lut, h_g2);
+  c4_emit(a.paw, rx | xy | xz | yz, lut, h_g2);
+  c4_emit(a.star, rx | xy | xz, lut, h_g2);
+  c4_emit(a.path, rx | xy | yz, lut, h_g2);
+}
+
+// ---------------------------------------------------------------- (c), order 4, hash set
+// The same shapes enumerated one set at a time with pair lookups in the hash
+// set (used when no bit rows are kept).  One wavefront per pair, lanes over y.
+__device__ inline void c4_hash_item(const View& v, uint32_t r, uint32_t x, const uint8_t* lut,
+                                    unsigned long long* h_g2) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const uint32_t* adj = v.g2_adj;
+  const uint32_t rb = v.g2_off[r], re = v.g2_off[r + 1];
+  const uint32_t xb = v.g2_off[x], xe = v.g2_off[x + 1];
+  const uint32_t p = upper_bound(adj, rb, re, x);
+  // |A| = 3 and |A| = 2
+  for (uint32_t yi = p + lane; yi < re; yi += kWave) {
+    const uint32_t y = adj[yi];
+    const uint32_t xy = has2(v.hs2, x, y);
+    for (uint32_t zi = yi + 1; zi < re; ++zi) {   // z > y, z ~ r
+      const uint32_t z = adj[zi];
+      const uint32_t pz = (1u << 0) | (1u << 1) | (xy << 2) | (1u << 4) | (uint32_t(has2(v.hs2, x, z)) << 5) |
+                          (uint32_t(has2(v.hs2, y, z)) << 7);
+      atomicAdd(&h_g2[lut[pz]], 1ull);
+    }
+    for (uint32_t zi = xb; zi < xe; ++zi) {       // z ~ x
+      const uint32_t z = adj[zi];
+      if (z <= r || z == y || has2(v.hs2, r, z)) continue;
+      const uint32_t pz = (1u << 0) | (1u << 1) | (xy << 2) | (1u << 5) | (uint32_t(has2(v.hs2, y, z)) << 7);
+      atomicAdd(&h_g2[lut[pz]], 1ull);
+    }
+    const uint32_t yb = v.g2_off[y], ye = v.g2_off[y + 1];
+    for (uint32_t zi = yb; zi < ye; ++zi) {       // z ~ y, z !~ x
+      const uint32_t z = adj[zi];
+      if (z <= r || z == x || has2(v.hs2, r, z) || has2(v.hs2, x, z)) continue;
+      const uint32_t pz = (1u << 0) | (1u << 1) | (xy << 2) | (1u << 7);
+      atomicAdd(&h_g2[lut[pz]], 1ull);
+    }
+  }
+  // |A| = 1
+  const uint32_t q = upper_bound(adj, xb, xe, r);
+  for (uint32_t yi = q + lane; yi < xe; yi += kWave) {
+    const uint32_t y = adj[yi];
+    if (has2(v.hs2, r, y)) continue;
+    for (uint32_t zi = yi + 1; zi < xe; ++zi) {   // z > y, z ~ x
+      const uint32_t z = adj[zi];
+      if (has2(v.hs2, r, z)) continue;
+      const uint32_t pz = (1u << 0) | (1u << 2) | (1u << 5) | (uint32_t(has2(v.hs2, y, z)) << 7);
+      atomicAdd(&h_g2[lut[pz]], 1ull);
+    }
+    const uint32_t yb = v.g2_off[y], ye = v.g2_off[y + 1];
+    for (uint32_t zi = yb; zi < ye; ++zi) {       // z ~ y, z !~ x, z !~ r, z > r
+      const uint32_t z = adj[zi];
+      if (z <= r || z == x || has2(v.hs2, r, z) || has2(v.hs2, x, z)) continue;
+      atomicAdd(&h_g2[lut[(1u << 0) | (1u << 2) | (1u << 7)]], 1ull);
+    }
+  }
+}
+
+// ---------------------------------------------------------------- (c), order 3
+// Connected triples of G2 from their smallest node r, for the pair {r < y}:
+// z > y both neighbours of r (triangle or wedge centred at r), or z > r a
+// neighbour of y only (wedge centred at y).  Local positions r=0, y=1, z=2.
+struct C3Acc {
+  unsigned long long tri, wedge_r, wedge_y;
+};
+
+__device__ inline void c3_bits_word(const View& v, uint32_t r, uint32_t y, uint32_t w, C3Acc& a) {
+  const uint32_t Nr = v.bits[uint64_t(r) * v.W + w], Ny = v.bits[uint64_t(y) * v.W + w];
+  const uint32_t z = Nr & mask_gt(y, w);
+  a.tri += __popc(z & Ny);
+  a.wedge_r += __popc(z & ~Ny);
+  a.wedge_y += __popc(Ny & ~Nr & mask_gt(r, w) & mask_below(v.N, w));
+}
+
+__device__ inline void c3_hash_item(const View& v, uint32_t r, uint32_t y, C3Acc& a) {
+  const uint32_t re = v.g2_off[r + 1];
+  for (uint32_t zi = upper_bound(v.g2_adj, v.g2_off[r], re, y); zi < re; ++zi) {
+    if (has2(v.hs2, y, v.g2_adj[zi])) ++a.tri; else ++a.wedge_r;
+  }
+  for (uint32_t zi = v.g2_off[y]; zi < v.g2_off[y + 1]; ++zi) {
+    const uint32_t z = v.g2_adj[zi];
+    if (z > r && !has2(v.hs2, r, z)) ++a.wedge_y;
+  }
+}
+
+// every lane of the wavefront must call this
+__device__ inline void c3_flush(const C3Acc& a, const uint8_t* lut, unsigned long long* h_g2) {
+  const unsigned long long s_tri = wave_sum(a.tri), s_wr = wave_sum(a.wedge_r), s_wy = wave_sum(a.wedge_y);
+  if ((threadIdx.x & (kWave - 1)) == 0) {
+    if (s_tri) atomicAdd(&h_g2[lut[7]], s_tri);
+    if (s_wr) atomicAdd(&h_g2[lut[3]], s_wr);
+    if (s_wy) atomicAdd(&h_g2[lut[5]], s_wy);
+  }
+}
+
+}  // namespace hm

@@ -17,7 +17,11 @@
 // copies (sd with n - 1) is formed in fp64 and rounded to fp32.
 #include <vector>
 
-#include "hm_device.h"
+#include <map>
+#include <mutex>
+#include <tuple>
+
+#include "hm_items.h"
 
 namespace hm {
 
@@ -27,8 +31,9 @@ namespace {
 
 constexpr int kMaxRepairRounds = 64;
 
-__global__ void k_null_keys(uint32_t c0, uint32_t R, uint64_t T, unsigned long long seed, unsigned long long* keys,
-                            uint32_t* vals) {
+__global__ void k_null_keys(uint32_t c0, uint32_t R, uint64_t T, const unsigned long long* __restrict__ seed_p,
+                            unsigned long long* keys, uint32_t* vals) {
+  const unsigned long long seed = *seed_p;
   const uint64_t n = uint64_t(R) * T;
   for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += uint64_t(gridDim.x) * blockDim.x) {
     const uint64_t c = i / T, t = i % T;
@@ -136,9 +141,11 @@ struct RepairScratch {
 // One workgroup per copy: repair rounds until no hyperedge repeats a node.
 __global__ void __launch_bounds__(kThreads) k_null_repair(uint32_t c0, uint32_t R, uint32_t E, uint64_t T,
                                                           const unsigned long long* __restrict__ off,
-                                                          uint32_t* __restrict__ members, unsigned long long seed,
+                                                          uint32_t* __restrict__ members,
+                                                          const unsigned long long* __restrict__ seed_p,
                                                           RepairScratch sc, uint32_t* __restrict__ failed) {
   __shared__ uint32_t wsum[kWavesPerBlock];
+  const unsigned long long seed = *seed_p;
   for (uint32_t c = blockIdx.x; c < R; c += gridDim.x) {
     uint32_t* m = members + uint64_t(c) * T;
     uint32_t* bad = sc.bad + uint64_t(blockIdx.x) * E;
@@ -261,21 +268,6 @@ unsigned grid_for(uint64_t n, unsigned cap = 4096) {
   return unsigned(g);
 }
 
-struct NullBuffers {
-  std::vector<void*> ptrs;
-  ~NullBuffers() {
-    for (void* p : ptrs) dfree(p);
-  }
-  template <typename T>
-  int get(T** p, uint64_t n) {
-    void* q = nullptr;
-    HM_TRY(dalloc(&q, size_t(n ? n : 1) * sizeof(T)));
-    ptrs.push_back(q);
-    *p = static_cast<T*>(q);
-    return HM_OK;
-  }
-};
-
 uint64_t pow2_at_least(uint64_t n) {
   uint64_t p = 1;
   while (p < n) p <<= 1;
@@ -288,58 +280,883 @@ int bits_for(uint64_t n) {
   return b;
 }
 
+// ---------------------------------------------------------------- batched ingest of the copies
+// Every copy has the size sequence of the unique hyperedges of H (offsets
+// `off`, E hyperedges, T members).  Index spaces run over (copy, hyperedge);
+// per-size outputs of all copies are concatenated copy by copy, and
+// incidence indices are positions in those concatenations.  Capacities come
+// from H (a copy cannot hold more hyperedges of a size than H), so nothing
+// depends on host-side counts.
+
+__device__ inline unsigned long long tuple_hash_b(const uint32_t* m, uint32_t s) {
+  unsigned long long h = mix64(0x51ed270b27a3ffb1ull ^ s);
+  for (uint32_t i = 0; i < s; ++i) h = mix64(h ^ (m[i] + 0x9e3779b97f4a7c15ull * (i + 1)));
+  return h;
+}
+
+__global__ void k_b_prepare(uint32_t R, uint32_t E, uint64_t T, const unsigned long long* __restrict__ off,
+                            uint32_t* __restrict__ members, unsigned long long* __restrict__ hash) {
+  const uint64_t n = uint64_t(R) * E;
+  for (uint64_t idx = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; idx < n; idx += uint64_t(gridDim.x) * blockDim.x) {
+    const uint64_t c = idx / E, i = idx % E;
+    const uint32_t s = uint32_t(off[i + 1] - off[i]);
+    if (s < 2 || s > 4) {
+      hash[idx] = 0;
+      continue;
+    }
+    uint32_t* m = members + c * T + off[i];
+    uint32_t r[4];
+    for (uint32_t j = 0; j < s; ++j) {
+      const uint32_t v = m[j];
+      uint32_t k = j;
+      while (k > 0 && r[k - 1] > v) {
+        r[k] = r[k - 1];
+        --k;
+      }
+      r[k] = v;
+    }
+    for (uint32_t j = 0; j < s; ++j) m[j] = r[j];
+    hash[idx] = tuple_hash_b(r, s);
+  }
+}
+
+__device__ inline bool same_copy_tuple(const uint32_t* mc, const unsigned long long* off, uint32_t a, uint32_t b) {
+  const uint32_t sa = uint32_t(off[a + 1] - off[a]);
+  if (sa != uint32_t(off[b + 1] - off[b])) return false;
+  const uint32_t* x = mc + off[a];
+  const uint32_t* y = mc + off[b];
+  for (uint32_t j = 0; j < sa; ++j)
+    if (x[j] != y[j]) return false;
+  return true;
+}
+
+__global__ void k_b_dedup(uint32_t R, uint32_t E, uint64_t T, const unsigned long long* __restrict__ off,
+                          const uint32_t* __restrict__ members, const unsigned long long* __restrict__ hash,
+                          uint32_t* __restrict__ tab, unsigned long long capD) {
+  const uint64_t n = uint64_t(R) * E;
+  for (uint64_t idx = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; idx < n; idx += uint64_t(gridDim.x) * blockDim.x) {
+    const uint64_t c = idx / E;
+    const uint32_t i = uint32_t(idx % E);
+    const uint32_t s = uint32_t(off[i + 1] - off[i]);
+    if (s < 2 || s > 4) continue;
+    uint32_t* t = tab + c * capD;
+    const uint32_t* mc = members + c * T;
+    unsigned long long pos = hash[idx] & (capD - 1);
+    while (true) {
+      uint32_t cur = t[pos];
+      if (cur == kEmpty32) {
+        const uint32_t prev = atomicCAS(&t[pos], kEmpty32, i);
+        if (prev == kEmpty32) break;
+        cur = prev;
+      }
+      if (hash[c * E + cur] == hash[idx] && same_copy_tuple(mc, off, cur, i)) {
+        atomicMin(&t[pos], i);
+        break;
+      }
+      pos = (pos + 1) & (capD - 1);
+    }
+  }
+}
+
+__global__ void k_b_first(uint32_t R, uint32_t E, uint64_t T, const unsigned long long* __restrict__ off,
+                          const uint32_t* __restrict__ members, const unsigned long long* __restrict__ hash,
+                          const uint32_t* __restrict__ tab, unsigned long long capD, uint32_t* f2, uint32_t* f3,
+                          uint32_t* f4) {
+  const uint64_t n = uint64_t(R) * E;
+  for (uint64_t idx = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; idx < n; idx += uint64_t(gridDim.x) * blockDim.x) {
+    const uint64_t c = idx / E;
+    const uint32_t i = uint32_t(idx % E);
+    const uint32_t s = uint32_t(off[i + 1] - off[i]);
+    bool first = false;
+    if (s >= 2 && s <= 4) {
+      const uint32_t* t = tab + c * capD;
+      const uint32_t* mc = members + c * T;
+      unsigned long long pos = hash[idx] & (capD - 1);
+      while (true) {
+        const uint32_t cur = t[pos];
+        if (cur == kEmpty32) break;
+        if (hash[c * E + cur] == hash[idx] && same_copy_tuple(mc, off, cur, i)) {
+          first = cur == i;
+          break;
+        }
+        pos = (pos + 1) & (capD - 1);
+      }
+    }
+    f2[idx] = first && s == 2;
+    f3[idx] = first && s == 3;
+    f4[idx] = first && s == 4;
+  }
+}
+
+__global__ void k_b_bases(uint32_t R, uint32_t E, const uint32_t* __restrict__ p2, const uint32_t* __restrict__ p3,
+                          const uint32_t* __restrict__ p4, const uint32_t* __restrict__ tot, uint32_t* base2,
+                          uint32_t* base3, uint32_t* base4) {
+  for (uint32_t c = blockIdx.x * blockDim.x + threadIdx.x; c <= R; c += gridDim.x * blockDim.x) {
+    base2[c] = c < R ? p2[uint64_t(c) * E] : tot[0];
+    base3[c] = c < R ? p3[uint64_t(c) * E] : tot[1];
+    base4[c] = c < R ? p4[uint64_t(c) * E] : tot[2];
+  }
+}
+
+__global__ void k_b_gather(uint32_t R, uint32_t E, uint64_t T, const unsigned long long* __restrict__ off,
+                           const uint32_t* __restrict__ members, const uint32_t* __restrict__ f2,
+                           const uint32_t* __restrict__ f3, const uint32_t* __restrict__ f4,
+                           const uint32_t* __restrict__ p2, const uint32_t* __restrict__ p3,
+                           const uint32_t* __restrict__ p4, uint32_t* e2, uint32_t* e3, uint32_t* e4, uint32_t* copy2,
+                           uint32_t* copy3, uint32_t* copy4) {
+  const uint64_t n = uint64_t(R) * E;
+  for (uint64_t idx = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; idx < n; idx += uint64_t(gridDim.x) * blockDim.x) {
+    const uint64_t c = idx / E, i = idx % E;
+    const uint32_t* m = members + c * T + off[i];
+    if (f2[idx]) {
+      const uint64_t q = p2[idx];
+      e2[2 * q] = m[0];
+      e2[2 * q + 1] = m[1];
+      copy2[q] = uint32_t(c);
+    } else if (f3[idx]) {
+      const uint64_t q = p3[idx];
+      for (int j = 0; j < 3; ++j) e3[3 * q + j] = m[j];
+      copy3[q] = uint32_t(c);
+    } else if (f4[idx]) {
+      const uint64_t q = p4[idx];
+      for (int j = 0; j < 4; ++j) e4[4 * q + j] = m[j];
+      copy4[q] = uint32_t(c);
+    }
+  }
+}
+
+__global__ void k_b_set64(uint64_t cap_items, const uint32_t* __restrict__ total, const uint32_t* __restrict__ e2,
+                          const uint32_t* __restrict__ copy2, unsigned long long* slots, unsigned long long cap) {
+  const uint64_t n = *total;
+  for (uint64_t q = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; q < n && q < cap_items;
+       q += uint64_t(gridDim.x) * blockDim.x) {
+    unsigned long long* s = slots + uint64_t(copy2[q]) * cap;
+    const unsigned long long key = key2(e2[2 * q], e2[2 * q + 1]);
+    unsigned long long pos = mix64(key) & (cap - 1);
+    while (atomicCAS(s + pos, kEmpty64, key) != kEmpty64) pos = (pos + 1) & (cap - 1);
+  }
+}
+
+template <int J>
+__global__ void k_b_set128(uint64_t cap_items, const uint32_t* __restrict__ total, const uint32_t* __restrict__ e,
+                           const uint32_t* __restrict__ copyj, unsigned long long* slots, unsigned long long cap) {
+  const uint64_t n = *total;
+  for (uint64_t q = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; q < n && q < cap_items;
+       q += uint64_t(gridDim.x) * blockDim.x) {
+    unsigned long long* s = slots + uint64_t(copyj[q]) * 2 * cap;
+    const uint32_t* t = e + J * q;
+    const Key128 key = (J == 3) ? key3(t[0], t[1], t[2]) : key4(t[0], t[1], t[2], t[3]);
+    unsigned long long pos = hash128(key) & (cap - 1);
+    while (atomicCAS(s + 2 * pos, kEmpty64, key.hi) != kEmpty64) pos = (pos + 1) & (cap - 1);
+    s[2 * pos + 1] = key.lo;
+  }
+}
+
+__global__ void k_b_pair_keys(uint64_t cap_items, const uint32_t* __restrict__ total, const uint32_t* __restrict__ e2,
+                              const uint32_t* __restrict__ copy2, uint32_t N, int B, unsigned long long* keys,
+                              uint32_t* vals, uint32_t* deg) {
+  const uint64_t n = *total;
+  for (uint64_t q = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; q < cap_items;
+       q += uint64_t(gridDim.x) * blockDim.x) {
+    vals[2 * q] = 0;
+    vals[2 * q + 1] = 0;
+    if (q >= n) {
+      keys[2 * q] = ~0ull;
+      keys[2 * q + 1] = ~0ull;
+      continue;
+    }
+    const unsigned long long c = copy2[q];
+    const uint32_t a = e2[2 * q], b = e2[2 * q + 1];
+    keys[2 * q] = (c << (2 * B)) | ((unsigned long long)a << B) | b;
+    keys[2 * q + 1] = (c << (2 * B)) | ((unsigned long long)b << B) | a;
+    atomicAdd(&deg[c * N + a], 1u);
+    atomicAdd(&deg[c * N + b], 1u);
+  }
+}
+
+__global__ void k_b_pair_adj(const unsigned long long* __restrict__ keys, uint64_t n, unsigned long long mask,
+                             uint32_t* adj) {
+  for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += uint64_t(gridDim.x) * blockDim.x)
+    adj[i] = uint32_t(keys[i] & mask);
+}
+
+template <int J>
+__global__ void k_b_inc_count(uint64_t cap_items, const uint32_t* __restrict__ total, const uint32_t* __restrict__ e,
+                              const uint32_t* __restrict__ copyj, uint32_t N, uint32_t* deg) {
+  const uint64_t n = *total;
+  for (uint64_t q = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; q < n && q < cap_items;
+       q += uint64_t(gridDim.x) * blockDim.x)
+    for (int j = 0; j < J; ++j) atomicAdd(&deg[uint64_t(copyj[q]) * N + e[J * q + j]], 1u);
+}
+
+template <int J>
+__global__ void k_b_inc_fill(uint64_t cap_items, const uint32_t* __restrict__ total, const uint32_t* __restrict__ e,
+                             const uint32_t* __restrict__ copyj, uint32_t N, uint32_t* cursor, uint32_t* idx) {
+  const uint64_t n = *total;
+  for (uint64_t q = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; q < n && q < cap_items;
+       q += uint64_t(gridDim.x) * blockDim.x)
+    for (int j = 0; j < J; ++j) idx[atomicAdd(&cursor[uint64_t(copyj[q]) * N + e[J * q + j]], 1u)] = uint32_t(q);
+}
+
+__global__ void k_b_bits(uint64_t cap_items, const uint32_t* __restrict__ total, const uint32_t* __restrict__ e2,
+                         const uint32_t* __restrict__ copy2, uint32_t N, uint32_t W, uint32_t* bits) {
+  const uint64_t n = *total;
+  for (uint64_t q = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; q < n && q < cap_items;
+       q += uint64_t(gridDim.x) * blockDim.x) {
+    uint32_t* b = bits + uint64_t(copy2[q]) * N * W;
+    const uint32_t u = e2[2 * q], v = e2[2 * q + 1];
+    atomicOr(&b[uint64_t(u) * W + (v >> 5)], 1u << (v & 31));
+    atomicOr(&b[uint64_t(v) * W + (u >> 5)], 1u << (u & 31));
+  }
+}
+
+// ---------------------------------------------------------------- persistent counting
+// Work is cut into tiles of one phase of one copy: phase 0 = (b) 3-node
+// hyperedges (a wavefront per item), phase 1 = (c) pairs (a wavefront per
+// item at order 4; a lane per item at order 3), phase 2 = (a) hyperedges of
+// size k (a lane per item).  Tiles are ordered phase-major, heaviest phase
+// first; every wavefront takes the next tile from an atomic counter until
+// none is left, so copies of uneven size share the machine.
+struct BatchView {
+  const uint32_t *e2, *e3, *e4, *g2_off, *g2_adj, *i3_off, *i3_idx, *i4_off, *i4_idx;
+  unsigned long long *hs2, *hs3, *hs4;
+  unsigned long long cap2, cap3, cap4;
+  const uint32_t* bits;
+  uint32_t W, N;
+  const uint32_t *base2, *base3, *base4;
+};
+
+__device__ inline View copy_view(const BatchView& b, uint32_t c) {
+  View v;
+  v.e2 = b.e2;
+  v.e3 = b.e3;
+  v.e4 = b.e4;
+  v.g2_off = b.g2_off + uint64_t(c) * b.N;
+  v.g2_adj = b.g2_adj;
+  v.i3_off = b.i3_off + uint64_t(c) * b.N;
+  v.i3_idx = b.i3_idx;
+  v.i4_off = b.i4_off + uint64_t(c) * b.N;
+  v.i4_idx = b.i4_idx;
+  v.hs2 = Set64{b.hs2 + uint64_t(c) * b.cap2, b.cap2 - 1};
+  v.hs3 = Set128{b.hs3 + uint64_t(c) * 2 * b.cap3, b.cap3 - 1};
+  v.hs4 = Set128{b.hs4 + uint64_t(c) * 2 * b.cap4, b.cap4 - 1};
+  v.bits = b.bits ? b.bits + uint64_t(c) * b.N * b.W : nullptr;
+  v.W = b.W;
+  v.N = b.N;
+  return v;
+}
+
+struct Chunks {
+  uint32_t per_tile[3];   // items per tile of each phase
+};
+
+__global__ void k_tile_counts(uint32_t R, int k, BatchView b, Chunks ch, uint32_t* counts) {
+  for (uint32_t s = blockIdx.x * blockDim.x + threadIdx.x; s < 3 * R; s += gridDim.x * blockDim.x) {
+    const uint32_t ph = s / R, c = s % R;
+    uint32_t items = 0;
+    if (ph == 0) items = k == 4 ? b.base3[c + 1] - b.base3[c] : 0;
+    if (ph == 1) items = b.base2[c + 1] - b.base2[c];
+    if (ph == 2) items = k == 4 ? b.base4[c + 1] - b.base4[c] : b.base3[c + 1] - b.base3[c];
+    counts[s] = (items + ch.per_tile[ph] - 1) / ch.per_tile[ph];
+  }
+}
+
+__global__ void __launch_bounds__(kThreads) k_null_count(BatchView b, uint32_t R, int k,
+                                                         const uint32_t* __restrict__ tile_prefix,
+                                                         uint32_t* __restrict__ counter, Chunks ch,
+                                                         const uint8_t* __restrict__ lut_g,
+                                                         unsigned long long* __restrict__ hist_all) {
+  __shared__ uint8_t lut[2048];
+  __shared__ unsigned long long wh[kWavesPerBlock][512];
+  __shared__ B4Scratch scratch[kWavesPerBlock];
+  __shared__ uint32_t ylist[kWavesPerBlock][kWave];
+  load_lut(lut, lut_g, k == 4 ? 2048 : 16);
+  __syncthreads();
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wv = threadIdx.x / kWave;
+  unsigned long long* h_main = wh[wv];
+  unsigned long long* h_sub = wh[wv] + 256;
+  const uint32_t total = tile_prefix[3 * R];
+  const C4Lanes L = c4_lanes(b.W);
+  while (true) {
+    uint32_t t = 0;
+    if (lane == 0) t = atomicAdd(counter, 1u);
+    t = __shfl(t, 0, kWave);
+    if (t >= total) break;
+    // the slot (phase, copy) whose tile range holds t
+    uint32_t lo = 0, hi = 3 * R;
+    while (hi - lo > 1) {
+      const uint32_t mid = (lo + hi) >> 1;
+      if (tile_prefix[mid] <= t) lo = mid; else hi = mid;
+    }
+    const uint32_t ph = lo / R, c = lo % R;
+    const uint32_t first = (t - tile_prefix[lo]) * ch.per_tile[ph];
+    const View v = copy_view(b, c);
+    unsigned long long* hc = hist_all + uint64_t(c) * kHistWords;
+    for (uint32_t i = lane; i < 512; i += kWave) wh[wv][i] = 0;
+    wave_sync();
+    if (ph == 0) {
+      const uint32_t n = b.base3[c + 1] - b.base3[c];
+      const uint32_t last = min(n, first + ch.per_tile[0]);
+      for (uint32_t j = first; j < last; ++j) b4_item(v, b.base3[c] + j, &scratch[wv], lut, h_main, h_sub);
+    } else if (ph == 1) {
+      const uint32_t n = b.base2[c + 1] - b.base2[c];
+      const uint32_t last = min(n, first + ch.per_tile[1]);
+      if (k == 4) {
+        if (v.bits) {
+          C4Acc acc;
+          c4_zero(acc);
+          for (uint32_t j = first; j < last; ++j) {
+            const uint64_t q = b.base2[c] + j;
+            c4_bits_item(v, b.e2[2 * q], b.e2[2 * q + 1], L, ylist[wv], acc);
+          }
+          c4_flush(acc, lut, hc + kG2);
+        } else {
+          for (uint32_t j = first; j < last; ++j) {
+            const uint64_t q = b.base2[c] + j;
+            c4_hash_item(v, b.e2[2 * q], b.e2[2 * q + 1], lut, h_main);
+          }
+        }
+      } else {
+        C3Acc acc{0, 0, 0};
+        for (uint32_t j = first + lane; j < last; j += kWave) {
+          const uint64_t q = b.base2[c] + j;
+          const uint32_t r = b.e2[2 * q], y = b.e2[2 * q + 1];
+          if (v.bits) {
+            for (uint32_t w = 0; w < v.W; ++w) c3_bits_word(v, r, y, w, acc);
+          } else {
+            c3_hash_item(v, r, y, acc);
+          }
+        }
+        c3_flush(acc, lut, hc + kG2);
+      }
+    } else {
+      if (k == 4) {
+        const uint32_t n = b.base4[c + 1] - b.base4[c];
+        const uint32_t last = min(n, first + ch.per_tile[2]);
+        for (uint32_t j = first + lane; j < last; j += kWave) {
+          const uint64_t q = b.base4[c] + j;
+          count_class(lut, h_main, h_sub, a4_pattern(v, b.e4[4 * q], b.e4[4 * q + 1], b.e4[4 * q + 2], b.e4[4 * q + 3]),
+                      kPairBits4);
+        }
+      } else {
+        const uint32_t n = b.base3[c + 1] - b.base3[c];
+        const uint32_t last = min(n, first + ch.per_tile[2]);
+        for (uint32_t j = first + lane; j < last; j += kWave) {
+          const uint64_t q = b.base3[c] + j;
+          count_class(lut, h_main, h_sub, a3_pattern(v, b.e3[3 * q], b.e3[3 * q + 1], b.e3[3 * q + 2]), kPairBits3);
+        }
+      }
+    }
+    wave_sync();
+    // wavefront counters -> the copy's counters; the hash-set variant of (c)
+    // at order 4 counts G2 shapes in the first half
+    const bool g2_in_main = (ph == 1 && k == 4 && !v.bits);
+    for (uint32_t i = lane; i < 512; i += kWave) {
+      const unsigned long long x = wh[wv][i];
+      if (!x) continue;
+      if (g2_in_main) {
+        if (i < 256) atomicAdd(hc + kG2 + i, x);
+      } else {
+        atomicAdd(hc + i, x);   // kMain = 0, kSub = 256
+      }
+    }
+    wave_sync();
+  }
+}
+
+struct ClassMaskB {
+  unsigned long long w[4];
+};
+
+__global__ void k_b_combine(const unsigned long long* __restrict__ hist_all, int n_classes, ClassMaskB pairs_only,
+                            int64_t* __restrict__ counts) {
+  const uint32_t c = blockIdx.x;
+  const int m = threadIdx.x;
+  if (m >= n_classes) return;
+  const unsigned long long* h = hist_all + uint64_t(c) * kHistWords;
+  unsigned long long v = h[kMain + m];
+  if ((pairs_only.w[m >> 6] >> (m & 63)) & 1ull) v += h[kG2 + m] - h[kSub + m];
+  counts[uint64_t(c) * n_classes + m] = int64_t(v);
+}
+
 }  // namespace
 
-// Generate copies [c0, c0 + R) into members (R x T, device).
+// ---------------------------------------------------------------- plan
+struct NullPlan {
+  int k = 0;
+  uint32_t R = 0, E = 0, N = 0;
+  uint64_t T = 0, n2H = 0, n3H = 0, n4H = 0;
+  int B = 0;
+  uint32_t W = 0;
+  bool use_bits = false;
+  unsigned long long capD = 0, cap2 = 0, cap3 = 0, cap4 = 0;
+  Chunks chunks{{4, 4, 256}};
+  uint32_t repair_blocks = 0;
+  // buffers
+  unsigned long long* seed = nullptr;
+  uint32_t* members = nullptr;
+  unsigned long long *skeys = nullptr, *skeys_tmp = nullptr;
+  uint32_t *svals = nullptr, *svals_tmp = nullptr;
+  uint32_t* sort_ws = nullptr;
+  RepairScratch rs{};
+  uint32_t* failed = nullptr;
+  unsigned long long* hash = nullptr;
+  uint32_t* dtab = nullptr;
+  uint32_t *f2 = nullptr, *f3 = nullptr, *f4 = nullptr, *p2 = nullptr, *p3 = nullptr, *p4 = nullptr;
+  uint32_t* tot = nullptr;
+  uint32_t* scan_ws = nullptr;
+  uint32_t *base2 = nullptr, *base3 = nullptr, *base4 = nullptr;
+  uint32_t *e2 = nullptr, *e3 = nullptr, *e4 = nullptr, *copy2 = nullptr, *copy3 = nullptr, *copy4 = nullptr;
+  unsigned long long *hs2 = nullptr, *hs3 = nullptr, *hs4 = nullptr;
+  unsigned long long *pkeys = nullptr, *pkeys_tmp = nullptr;
+  uint32_t *pvals = nullptr, *pvals_tmp = nullptr;
+  uint32_t *deg = nullptr, *cursor = nullptr;
+  uint32_t *g2_off = nullptr, *g2_adj = nullptr, *i3_off = nullptr, *i3_idx = nullptr, *i4_off = nullptr,
+           *i4_idx = nullptr;
+  uint32_t* bits = nullptr;
+  unsigned long long* hist_all = nullptr;
+  uint32_t *tile_counts = nullptr, *tile_prefix = nullptr, *tile_counter = nullptr;
+  int64_t *real = nullptr, *nulls = nullptr;
+  float* z = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::vector<void*> allocs;
+
+  template <typename T>
+  int get(T** p, uint64_t n) {
+    void* q = nullptr;
+    HM_TRY(dalloc(&q, size_t(n ? n : 1) * sizeof(T)));
+    allocs.push_back(q);
+    *p = static_cast<T*>(q);
+    return HM_OK;
+  }
+  ~NullPlan() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    (void)hipDeviceSynchronize();
+    for (void* p : allocs) dfree(p);
+  }
+};
+
+void destroy_null_plan(NullPlan* p) { delete p; }
+
+namespace {
+
+BatchView batch_view(const NullPlan& P) {
+  BatchView b;
+  b.e2 = P.e2;
+  b.e3 = P.e3;
+  b.e4 = P.e4;
+  b.g2_off = P.g2_off;
+  b.g2_adj = P.g2_adj;
+  b.i3_off = P.i3_off;
+  b.i3_idx = P.i3_idx;
+  b.i4_off = P.i4_off;
+  b.i4_idx = P.i4_idx;
+  b.hs2 = P.hs2;
+  b.hs3 = P.hs3;
+  b.hs4 = P.hs4;
+  b.cap2 = P.cap2;
+  b.cap3 = P.cap3;
+  b.cap4 = P.cap4;
+  b.bits = P.use_bits ? P.bits : nullptr;
+  b.W = P.W;
+  b.N = P.N;
+  b.base2 = P.base2;
+  b.base3 = P.base3;
+  b.base4 = P.base4;
+  return b;
+}
+
+int make_plan(const hm_graph* H, int k, uint32_t R, NullPlan** out) {
+  NullPlan* P = new (std::nothrow) NullPlan();
+  if (!P) {
+    set_error("host allocation failed");
+    return HM_ENOMEM;
+  }
+  P->k = k;
+  P->R = R;
+  P->E = uint32_t(H->n_unique);
+  P->T = H->n_unique_members;
+  P->N = H->n_nodes;
+  P->n2H = H->n_by_size[2];
+  P->n3H = H->n_by_size[3];
+  P->n4H = H->n_by_size[4];
+  P->B = bits_for(P->N);
+  P->use_bits = H->bits != nullptr;
+  P->W = P->use_bits ? H->words : 0;
+  P->capD = pow2_capacity(P->E);
+  P->cap2 = pow2_capacity(P->n2H);
+  P->cap3 = pow2_capacity(P->n3H);
+  P->cap4 = pow2_capacity(P->n4H);
+  const uint64_t RT = uint64_t(R) * P->T, RE = uint64_t(R) * P->E, RN = uint64_t(R) * P->N;
+  const uint64_t m2 = uint64_t(R) * P->n2H, m3 = uint64_t(R) * P->n3H, m4 = uint64_t(R) * P->n4H;
+  auto fail = [&](int rc) {
+    delete P;
+    return rc;
+  };
+  if (RT >= 0xFFFFFFFFull || RE >= 0xFFFFFFFFull || 2 * m2 >= 0xFFFFFFFFull || RN >= 0xFFFFFFFFull ||
+      2 * P->B + bits_for(R) > 64) {
+    set_error("null batch too large (%u copies)", R);
+    return fail(HM_EUNSUPPORTED);
+  }
+  int rc = HM_OK;
+#define GET(ptr, n) \
+  if (rc == HM_OK) rc = P->get(&(ptr), (n))
+  GET(P->seed, 1);
+  GET(P->members, RT);
+  GET(P->skeys, RT);
+  GET(P->skeys_tmp, RT);
+  GET(P->svals, RT);
+  GET(P->svals_tmp, RT);
+  const uint64_t sort_words = std::max(radix_ws_words(RT), radix_ws_words(2 * m2 + 2));
+  GET(P->sort_ws, sort_words);
+  P->repair_blocks = R < 256 ? R : 256;
+  P->rs.chosen_pad = pow2_at_least(2ull * P->E + 2);
+  P->rs.pool_pad = pow2_at_least(P->T + 1);
+  GET(P->rs.bad, uint64_t(P->repair_blocks) * P->E + 1);
+  GET(P->rs.chosen, uint64_t(P->repair_blocks) * P->rs.chosen_pad);
+  GET(P->rs.off, uint64_t(P->repair_blocks) * P->rs.chosen_pad);
+  GET(P->rs.key, uint64_t(P->repair_blocks) * P->rs.pool_pad);
+  GET(P->rs.aux, uint64_t(P->repair_blocks) * P->rs.pool_pad);
+  GET(P->rs.val, uint64_t(P->repair_blocks) * P->rs.pool_pad);
+  GET(P->failed, 1);
+  GET(P->hash, RE);
+  GET(P->dtab, uint64_t(R) * P->capD);
+  GET(P->f2, RE);
+  GET(P->f3, RE);
+  GET(P->f4, RE);
+  GET(P->p2, RE);
+  GET(P->p3, RE);
+  GET(P->p4, RE);
+  GET(P->tot, 4);
+  GET(P->scan_ws, std::max(scan_ws_words(RE), scan_ws_words(RN + 1)) + scan_ws_words(3ull * R + 1));
+  GET(P->base2, uint64_t(R) + 1);
+  GET(P->base3, uint64_t(R) + 1);
+  GET(P->base4, uint64_t(R) + 1);
+  GET(P->e2, 2 * m2);
+  GET(P->e3, 3 * m3);
+  GET(P->e4, 4 * m4);
+  GET(P->copy2, m2);
+  GET(P->copy3, m3);
+  GET(P->copy4, m4);
+  GET(P->hs2, uint64_t(R) * P->cap2);
+  GET(P->hs3, uint64_t(R) * 2 * P->cap3);
+  GET(P->hs4, uint64_t(R) * 2 * P->cap4);
+  GET(P->pkeys, 2 * m2 + 2);
+  GET(P->pkeys_tmp, 2 * m2 + 2);
+  GET(P->pvals, 2 * m2 + 2);
+  GET(P->pvals_tmp, 2 * m2 + 2);
+  GET(P->deg, RN);
+  GET(P->cursor, RN);
+  GET(P->g2_off, RN + 1);
+  GET(P->g2_adj, 2 * m2 + 2);
+  GET(P->i3_off, RN + 1);
+  GET(P->i3_idx, 3 * m3);
+  GET(P->i4_off, RN + 1);
+  GET(P->i4_idx, 4 * m4);
+  if (P->use_bits) GET(P->bits, RN * P->W);
+  GET(P->hist_all, uint64_t(R) * kHistWords);
+  GET(P->tile_counts, 3ull * R + 1);
+  GET(P->tile_prefix, 3ull * R + 1);
+  GET(P->tile_counter, 1);
+  const int C = class_tables().n_classes[k];
+  GET(P->real, uint64_t(C));
+  GET(P->nulls, uint64_t(R) * C);
+  GET(P->z, uint64_t(C));
+#undef GET
+  if (rc != HM_OK) return fail(rc);
+  *out = P;
+  return HM_OK;
+}
+
+// Stub matching of copies c0 .. c0+R-1 into P.members (no allocation, no sync).
+int enqueue_stubs(const hm_graph* H, NullPlan& P, uint32_t c0, hipStream_t st) {
+  const uint64_t n = uint64_t(P.R) * P.T;
+  if (n == 0) return HM_OK;
+  k_null_keys<<<grid_for(n), 256, 0, st>>>(c0, P.R, P.T, P.seed, P.skeys, P.svals);
+  HM_HIP(hipGetLastError());
+  HM_TRY(radix_sort_ws(P.skeys, P.svals, P.skeys_tmp, P.svals_tmp, n, 64, P.sort_ws, st));
+  if (P.R > 1) {
+    k_copy_of<<<grid_for(n), 256, 0, st>>>(P.svals, n, P.T, P.skeys);
+    HM_HIP(hipGetLastError());
+    HM_TRY(radix_sort_ws(P.skeys, P.svals, P.skeys_tmp, P.svals_tmp, n, bits_for(P.R), P.sort_ws, st));
+  }
+  k_null_gather<<<grid_for(n), 256, 0, st>>>(P.svals, n, P.T, H->all_members, P.members);
+  HM_HIP(hipGetLastError());
+  HM_TRY(fill_u32(P.failed, 0, 1, st));
+  k_null_repair<<<P.repair_blocks, kThreads, 0, st>>>(c0, P.R, P.E, P.T, H->all_off, P.members, P.seed, P.rs,
+                                                      P.failed);
+  HM_HIP(hipGetLastError());
+  return HM_OK;
+}
+
+// Batched ingest of the copies in P.members.
+int enqueue_ingest(const hm_graph* H, NullPlan& P, hipStream_t st) {
+  const uint32_t R = P.R, E = P.E, N = P.N;
+  const uint64_t RE = uint64_t(R) * E, RN = uint64_t(R) * N;
+  const uint64_t m2 = uint64_t(R) * P.n2H, m3 = uint64_t(R) * P.n3H, m4 = uint64_t(R) * P.n4H;
+  k_b_prepare<<<grid_for(RE), 256, 0, st>>>(R, E, P.T, H->all_off, P.members, P.hash);
+  HM_TRY(fill_u32(P.dtab, kEmpty32, uint64_t(R) * P.capD, st));
+  k_b_dedup<<<grid_for(RE), 256, 0, st>>>(R, E, P.T, H->all_off, P.members, P.hash, P.dtab, P.capD);
+  k_b_first<<<grid_for(RE), 256, 0, st>>>(R, E, P.T, H->all_off, P.members, P.hash, P.dtab, P.capD, P.f2, P.f3,
+                                          P.f4);
+  HM_HIP(hipGetLastError());
+  HM_TRY(scan_u32_ws(P.f2, P.p2, RE, P.tot + 0, P.scan_ws, st));
+  HM_TRY(scan_u32_ws(P.f3, P.p3, RE, P.tot + 1, P.scan_ws, st));
+  HM_TRY(scan_u32_ws(P.f4, P.p4, RE, P.tot + 2, P.scan_ws, st));
+  k_b_bases<<<grid_for(R + 1), 256, 0, st>>>(R, E, P.p2, P.p3, P.p4, P.tot, P.base2, P.base3, P.base4);
+  k_b_gather<<<grid_for(RE), 256, 0, st>>>(R, E, P.T, H->all_off, P.members, P.f2, P.f3, P.f4, P.p2, P.p3, P.p4, P.e2,
+                                           P.e3, P.e4, P.copy2, P.copy3, P.copy4);
+  HM_HIP(hipGetLastError());
+  HM_TRY(fill_u64(P.hs2, kEmpty64, uint64_t(R) * P.cap2, st));
+  HM_TRY(fill_u64(P.hs3, kEmpty64, uint64_t(R) * 2 * P.cap3, st));
+  HM_TRY(fill_u64(P.hs4, kEmpty64, uint64_t(R) * 2 * P.cap4, st));
+  if (m2) k_b_set64<<<grid_for(m2), 256, 0, st>>>(m2, P.tot + 0, P.e2, P.copy2, P.hs2, P.cap2);
+  if (m3) k_b_set128<3><<<grid_for(m3), 256, 0, st>>>(m3, P.tot + 1, P.e3, P.copy3, P.hs3, P.cap3);
+  if (m4) k_b_set128<4><<<grid_for(m4), 256, 0, st>>>(m4, P.tot + 2, P.e4, P.copy4, P.hs4, P.cap4);
+  HM_HIP(hipGetLastError());
+  // pairwise graph rows (ascending) of every copy
+  HM_TRY(fill_u32(P.deg, 0, RN, st));
+  if (m2) {
+    k_b_pair_keys<<<grid_for(m2), 256, 0, st>>>(m2, P.tot + 0, P.e2, P.copy2, N, P.B, P.pkeys, P.pvals, P.deg);
+    HM_HIP(hipGetLastError());
+    HM_TRY(radix_sort_ws(P.pkeys, P.pvals, P.pkeys_tmp, P.pvals_tmp, 2 * m2, 2 * P.B + bits_for(R), P.sort_ws, st));
+    k_b_pair_adj<<<grid_for(2 * m2), 256, 0, st>>>(P.pkeys, 2 * m2, (1ull << P.B) - 1, P.g2_adj);
+    HM_HIP(hipGetLastError());
+  }
+  HM_TRY(scan_u32_ws(P.deg, P.g2_off, RN, P.g2_off + RN, P.scan_ws, st));
+  // incident 3- and 4-node hyperedges
+  HM_TRY(fill_u32(P.deg, 0, RN, st));
+  if (m3) k_b_inc_count<3><<<grid_for(m3), 256, 0, st>>>(m3, P.tot + 1, P.e3, P.copy3, N, P.deg);
+  HM_HIP(hipGetLastError());
+  HM_TRY(scan_u32_ws(P.deg, P.i3_off, RN, P.i3_off + RN, P.scan_ws, st));
+  HM_TRY(copy_u32(P.i3_off, P.cursor, RN, st));
+  if (m3) k_b_inc_fill<3><<<grid_for(m3), 256, 0, st>>>(m3, P.tot + 1, P.e3, P.copy3, N, P.cursor, P.i3_idx);
+  HM_TRY(fill_u32(P.deg, 0, RN, st));
+  if (m4) k_b_inc_count<4><<<grid_for(m4), 256, 0, st>>>(m4, P.tot + 2, P.e4, P.copy4, N, P.deg);
+  HM_HIP(hipGetLastError());
+  HM_TRY(scan_u32_ws(P.deg, P.i4_off, RN, P.i4_off + RN, P.scan_ws, st));
+  HM_TRY(copy_u32(P.i4_off, P.cursor, RN, st));
+  if (m4) k_b_inc_fill<4><<<grid_for(m4), 256, 0, st>>>(m4, P.tot + 2, P.e4, P.copy4, N, P.cursor, P.i4_idx);
+  HM_HIP(hipGetLastError());
+  if (P.use_bits) {
+    HM_TRY(fill_u32(P.bits, 0, RN * P.W, st));
+    if (m2) k_b_bits<<<grid_for(m2), 256, 0, st>>>(m2, P.tot + 0, P.e2, P.copy2, N, P.W, P.bits);
+    HM_HIP(hipGetLastError());
+  }
+  return HM_OK;
+}
+
+unsigned persistent_grid() {
+  static unsigned g = 0;
+  if (!g) {
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    g = unsigned(cus > 0 ? cus : 256) * 2;
+  }
+  return g;
+}
+
+int enqueue_count(const hm_graph* H, NullPlan& P, const Chunks& ch, hipStream_t st) {
+  const uint8_t *lut4 = nullptr, *lut3 = nullptr;
+  HM_TRY(device_luts(H->device, &lut4, &lut3));
+  const BatchView bv = batch_view(P);
+  const uint32_t R = P.R;
+  k_tile_counts<<<grid_for(3ull * R), 256, 0, st>>>(R, P.k, bv, ch, P.tile_counts);
+  HM_HIP(hipGetLastError());
+  HM_TRY(scan_u32_ws(P.tile_counts, P.tile_prefix, 3ull * R, P.tile_prefix + 3ull * R, P.scan_ws, st));
+  HM_TRY(fill_u64(P.hist_all, 0, uint64_t(R) * kHistWords, st));
+  HM_TRY(fill_u32(P.tile_counter, 0, 1, st));
+  k_null_count<<<persistent_grid(), kThreads, 0, st>>>(bv, R, P.k, P.tile_prefix, P.tile_counter, ch,
+                                                       P.k == 4 ? lut4 : lut3, P.hist_all);
+  HM_HIP(hipGetLastError());
+  const ClassTables& t = class_tables();
+  ClassMaskB pairs_only{{0, 0, 0, 0}};
+  for (int c = 0; c < t.n_classes[P.k]; ++c)
+    if (t.maxcard[P.k][c] == 2) pairs_only.w[c >> 6] |= 1ull << (c & 63);
+  k_b_combine<<<R, 256, 0, st>>>(P.hist_all, t.n_classes[P.k], pairs_only, P.nulls);
+  HM_HIP(hipGetLastError());
+  return HM_OK;
+}
+
+int enqueue_all(const hm_graph* H, NullPlan& P, hipStream_t st) {
+  HM_TRY(count_exact_impl(H, P.k, P.real, st));
+  HM_TRY(enqueue_stubs(H, P, 0, st));
+  HM_TRY(enqueue_ingest(H, P, st));
+  HM_TRY(enqueue_count(H, P, P.chunks, st));
+  const int C = class_tables().n_classes[P.k];
+  k_zscore<<<1, 256, 0, st>>>(P.real, P.nulls, P.R, C, P.z);
+  HM_HIP(hipGetLastError());
+  return HM_OK;
+}
+
+// ---------------------------------------------------------------- autotuner
+// Items per tile of phases (b) and (c) are picked by timing the persistent
+// counting kernel on the ingested copies; choices are cached per device and
+// shape signature for the life of the process.
+using TuneKey = std::tuple<int, int, uint32_t, uint32_t, uint64_t, uint64_t, uint64_t, uint32_t, bool>;
+std::mutex g_tune_mu;
+std::map<TuneKey, Chunks> g_tuned;
+
+int autotune(const hm_graph* H, NullPlan& P, hipStream_t st) {
+  const TuneKey key{H->device, P.k, P.R, P.N, P.n2H, P.n3H, P.n4H, P.E, P.use_bits};
+  {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    auto it = g_tuned.find(key);
+    if (it != g_tuned.end()) {
+      P.chunks = it->second;
+      return HM_OK;
+    }
+  }
+  static const uint32_t cand_b[] = {1, 2, 4, 8, 16};
+  static const uint32_t cand_c[] = {1, 2, 4, 8, 16};
+  hipEvent_t e0, e1;
+  HM_HIP(hipEventCreate(&e0));
+  HM_HIP(hipEventCreate(&e1));
+  float best = 1e30f;
+  Chunks best_ch = P.chunks;
+  for (uint32_t cb : cand_b)
+    for (uint32_t cc : cand_c) {
+      Chunks ch{{cb, cc, P.k == 4 ? 256u : 1024u}};
+      if (P.k == 3) ch.per_tile[1] = 64 * cc;
+      float total = 0.f;
+      for (int rep = 0; rep < 2; ++rep) {
+        HM_HIP(hipEventRecord(e0, st));
+        HM_TRY(enqueue_count(H, P, ch, st));
+        HM_HIP(hipEventRecord(e1, st));
+        HM_HIP(hipEventSynchronize(e1));
+        float ms = 0.f;
+        HM_HIP(hipEventElapsedTime(&ms, e0, e1));
+        if (rep) total += ms;
+      }
+      if (total < best) {
+        best = total;
+        best_ch = ch;
+      }
+      if (P.k == 3) break;   // order 3: one lane per pair; only (c) chunking matters
+    }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  P.chunks = best_ch;
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  g_tuned[key] = best_ch;
+  return HM_OK;
+}
+
+}  // namespace
+
+// Generate copies [c0, c0 + R) into members (R x T, device), synchronously.
 int null_copies(const hm_graph* H, uint32_t c0, uint32_t R, uint64_t seed, uint32_t* members, hipStream_t st) {
-  const uint64_t T = H->n_unique_members;
-  const uint32_t E = uint32_t(H->n_unique);
-  if (T == 0 || R == 0) return HM_OK;
-  const uint64_t n = uint64_t(R) * T;
-  if (n >= 0xFFFFFFFFull) {
-    set_error("null batch of %llu stubs is too large", (unsigned long long)n);
+  if (H->n_unique_members == 0 || R == 0) return HM_OK;
+  NullPlan P;
+  P.R = R;
+  P.E = uint32_t(H->n_unique);
+  P.T = H->n_unique_members;
+  const uint64_t RT = uint64_t(R) * P.T;
+  if (RT >= 0xFFFFFFFFull) {
+    set_error("null batch too large");
     return HM_EUNSUPPORTED;
   }
-  NullBuffers b;
-  unsigned long long *keys, *keys_tmp;
-  uint32_t *vals, *vals_tmp, *failed;
-  HM_TRY(b.get(&keys, n));
-  HM_TRY(b.get(&keys_tmp, n));
-  HM_TRY(b.get(&vals, n));
-  HM_TRY(b.get(&vals_tmp, n));
-  HM_TRY(b.get(&failed, 1));
-  // round 0: stable sort by key within each copy (key sort, then a stable sort by copy)
-  k_null_keys<<<grid_for(n), 256, 0, st>>>(c0, R, T, seed, keys, vals);
-  HM_HIP(hipGetLastError());
-  HM_TRY(radix_sort_pairs(keys, vals, keys_tmp, vals_tmp, n, 64, st));
-  if (R > 1) {
-    k_copy_of<<<grid_for(n), 256, 0, st>>>(vals, n, T, keys);
-    HM_HIP(hipGetLastError());
-    HM_TRY(radix_sort_pairs(keys, vals, keys_tmp, vals_tmp, n, bits_for(R), st));
-  }
-  k_null_gather<<<grid_for(n), 256, 0, st>>>(vals, n, T, H->all_members, members);
-  HM_HIP(hipGetLastError());
-  // repair rounds, one workgroup per copy
-  const uint32_t blocks = R < 256 ? R : 256;
-  RepairScratch sc;
-  sc.chosen_pad = pow2_at_least(2ull * E + 2);
-  sc.pool_pad = pow2_at_least(T + 1);
-  HM_TRY(b.get(&sc.bad, uint64_t(blocks) * E + 1));
-  HM_TRY(b.get(&sc.chosen, uint64_t(blocks) * sc.chosen_pad));
-  HM_TRY(b.get(&sc.off, uint64_t(blocks) * sc.chosen_pad));
-  HM_TRY(b.get(&sc.key, uint64_t(blocks) * sc.pool_pad));
-  HM_TRY(b.get(&sc.aux, uint64_t(blocks) * sc.pool_pad));
-  HM_TRY(b.get(&sc.val, uint64_t(blocks) * sc.pool_pad));
-  HM_TRY(fill_u32(failed, 0, 1, st));
-  k_null_repair<<<blocks, kThreads, 0, st>>>(c0, R, E, T, H->all_off, members, seed, sc, failed);
-  HM_HIP(hipGetLastError());
+  HM_TRY(P.get(&P.seed, 1));
+  HM_TRY(P.get(&P.skeys, RT));
+  HM_TRY(P.get(&P.skeys_tmp, RT));
+  HM_TRY(P.get(&P.svals, RT));
+  HM_TRY(P.get(&P.svals_tmp, RT));
+  HM_TRY(P.get(&P.sort_ws, radix_ws_words(RT)));
+  P.repair_blocks = R < 256 ? R : 256;
+  P.rs.chosen_pad = pow2_at_least(2ull * P.E + 2);
+  P.rs.pool_pad = pow2_at_least(P.T + 1);
+  HM_TRY(P.get(&P.rs.bad, uint64_t(P.repair_blocks) * P.E + 1));
+  HM_TRY(P.get(&P.rs.chosen, uint64_t(P.repair_blocks) * P.rs.chosen_pad));
+  HM_TRY(P.get(&P.rs.off, uint64_t(P.repair_blocks) * P.rs.chosen_pad));
+  HM_TRY(P.get(&P.rs.key, uint64_t(P.repair_blocks) * P.rs.pool_pad));
+  HM_TRY(P.get(&P.rs.aux, uint64_t(P.repair_blocks) * P.rs.pool_pad));
+  HM_TRY(P.get(&P.rs.val, uint64_t(P.repair_blocks) * P.rs.pool_pad));
+  HM_TRY(P.get(&P.failed, 1));
+  P.members = members;
+  unsigned long long s = seed;
+  HM_HIP(hipMemcpyAsync(P.seed, &s, sizeof(s), hipMemcpyHostToDevice, st));
+  HM_TRY(enqueue_stubs(H, P, c0, st));
   uint32_t host_failed = 0;
-  HM_HIP(hipMemcpyAsync(&host_failed, failed, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+  HM_HIP(hipMemcpyAsync(&host_failed, P.failed, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
   HM_HIP(hipStreamSynchronize(st));
   if (host_failed) {
     set_error("stub matching: a hyperedge still repeats a node after %d repair rounds", kMaxRepairRounds);
     return HM_EINVAL;
   }
+  return HM_OK;
+}
+
+int count_nulls_impl(hm_graph* H, int k, uint32_t R, uint64_t seed, int64_t* real, int64_t* nulls, float* z,
+                     hipStream_t st) {
+  const int C = class_tables().n_classes[k];
+  const uint8_t *lut4 = nullptr, *lut3 = nullptr;
+  HM_TRY(device_luts(H->device, &lut4, &lut3));
+  if (H->n_unique == 0) {   // nothing to randomise: every count is zero
+    if (real) HM_TRY(count_exact_impl(H, k, real, st));
+    HM_TRY(fill_u64(reinterpret_cast<unsigned long long*>(nulls), 0, uint64_t(R) * C, st));
+    if (z) HM_TRY(fill_u32(reinterpret_cast<uint32_t*>(z), 0, uint64_t(C), st));
+    HM_HIP(hipStreamSynchronize(st));
+    return HM_OK;
+  }
+  NullPlan* P = H->null_plan;
+  if (P && (P->k != k || P->R != R)) {
+    destroy_null_plan(P);
+    H->null_plan = P = nullptr;
+  }
+  if (!P) {
+    HM_TRY(make_plan(H, k, R, &P));
+    H->null_plan = P;
+    // first run outside a graph: ingest the copies once and tune the tile sizes
+    unsigned long long s0 = seed;
+    HM_HIP(hipMemcpyAsync(P->seed, &s0, sizeof(s0), hipMemcpyHostToDevice, st));
+    HM_TRY(enqueue_stubs(H, *P, 0, st));
+    HM_TRY(enqueue_ingest(H, *P, st));
+    HM_TRY(autotune(H, *P, st));
+    // capture the whole pipeline once; later calls replay it
+    hipStream_t cs = nullptr;
+    HM_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    capture_begin();
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    int rc = e == hipSuccess ? enqueue_all(H, *P, cs) : HM_EDEVICE;
+    hipGraph_t g = nullptr;
+    const hipError_t e2 = hipStreamEndCapture(cs, &g);
+    capture_end();
+    if (rc == HM_OK && e2 != hipSuccess) rc = HM_EDEVICE;
+    if (rc == HM_OK && hipGraphInstantiate(&P->exec, g, nullptr, nullptr, 0) != hipSuccess) rc = HM_EDEVICE;
+    P->graph = g;
+    (void)hipStreamDestroy(cs);
+    if (rc != HM_OK) {
+      if (rc == HM_EDEVICE) set_error("capturing the null-model pipeline failed");
+      destroy_null_plan(P);
+      H->null_plan = nullptr;
+      return rc;
+    }
+  }
+  unsigned long long s = seed;
+  HM_HIP(hipMemcpyAsync(P->seed, &s, sizeof(s), hipMemcpyHostToDevice, st));
+  {
+    ProfileScope ps("null_pipeline_graph", st);
+    HM_HIP(hipGraphLaunch(P->exec, st));
+  }
+  if (real) HM_TRY(copy_u64(reinterpret_cast<const unsigned long long*>(P->real), reinterpret_cast<unsigned long long*>(real), uint64_t(C), st));
+  HM_TRY(copy_u64(reinterpret_cast<const unsigned long long*>(P->nulls), reinterpret_cast<unsigned long long*>(nulls), uint64_t(R) * C, st));
+  if (z) HM_TRY(copy_u32(reinterpret_cast<const uint32_t*>(P->z), reinterpret_cast<uint32_t*>(z), uint64_t(C), st));
+  uint32_t host_failed = 0;
+  HM_HIP(hipMemcpyAsync(&host_failed, P->failed, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+  HM_HIP(hipStreamSynchronize(st));
+  if (host_failed) {
+    set_error("stub matching: a hyperedge still repeats a node after %d repair rounds", kMaxRepairRounds);
+    return HM_EINVAL;
+  }
+  return HM_OK;
+}
+
+int null_tuned_chunks(const hm_graph* H, uint32_t* out3) {
+  if (!H->null_plan) return HM_EINVAL;
+  for (int i = 0; i < 3; ++i) out3[i] = H->null_plan->chunks.per_tile[i];
   return HM_OK;
 }
 
@@ -381,30 +1198,19 @@ int count_nulls(const hm_graph* H, int k, int n_rand, uint64_t seed, int64_t* re
     hm::set_error("n_rand must be in [2, 65535]");
     return HM_EINVAL;
   }
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  const int C = hm_num_classes(k);
-  const uint64_t T = H->n_unique_members;
-  hm::NullBuffers b;
-  int64_t* real_buf = real;
-  if (!real_buf) HM_TRY(b.get(&real_buf, uint64_t(C)));
-  HM_TRY(hm::count_exact_impl(H, k, real_buf, st));
-  uint32_t* members = nullptr;
-  HM_TRY(b.get(&members, uint64_t(n_rand) * T + 1));
-  HM_TRY(hm::null_copies(H, 0, uint32_t(n_rand), seed, members, st));
-  for (int c = 0; c < n_rand; ++c) {
-    hm_graph* G = nullptr;
-    HM_TRY(hm_graph_create(members + uint64_t(c) * T, reinterpret_cast<const uint64_t*>(H->all_off), H->n_unique,
-                           H->n_nodes, HM_MEM_DEVICE, stream, &G));
-    int rc = hm::count_exact_impl(G, k, nulls + uint64_t(c) * C, st);
-    if (rc == HM_OK && hipStreamSynchronize(st) != hipSuccess) rc = HM_EDEVICE;
-    hm_graph_destroy(G);
-    if (rc != HM_OK) return rc;
+  return hm::count_nulls_impl(const_cast<hm_graph*>(H), k, uint32_t(n_rand), seed, real, nulls, z,
+                              static_cast<hipStream_t>(stream));
+}
+
+int hm_null_tile_sizes(const hm_graph* H, uint32_t* out3) {
+  if (!H || !out3) {
+    hm::set_error("NULL argument");
+    return HM_EINVAL;
   }
-  if (z) {
-    hm::k_zscore<<<1, 256, 0, st>>>(real_buf, nulls, uint32_t(n_rand), C, z);
-    HM_HIP(hipGetLastError());
+  if (hm::null_tuned_chunks(H, out3) != HM_OK) {
+    hm::set_error("count_nulls has not run on this graph");
+    return HM_EINVAL;
   }
-  HM_HIP(hipStreamSynchronize(st));
   return HM_OK;
 }
 

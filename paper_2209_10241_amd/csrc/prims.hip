@@ -1,5 +1,7 @@
 // Device primitives used while building graphs: exclusive scans, a stable
 // LSD radix sort of (64-bit key, 32-bit value) pairs and fills.
+#include <algorithm>
+
 #include "hm_internal.h"
 
 namespace hm {
@@ -197,7 +199,104 @@ int fill_impl(T* p, T value, uint64_t n, hipStream_t st) {
   return HM_OK;
 }
 
+template <typename T>
+__global__ void k_copy(const T* __restrict__ src, T* __restrict__ dst, uint64_t n) {
+  for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += uint64_t(gridDim.x) * blockDim.x)
+    dst[i] = src[i];
+}
+
 }  // namespace
+
+// ------------------------------------------------------------------ planned (workspace) variants
+// Multi-level exclusive scan of up to n uint32 values: level l scans the
+// block sums of level l-1.  No allocation and no host synchronisation.
+uint64_t scan_ws_words(uint64_t n) {
+  uint64_t words = 0;
+  while (n > uint64_t(kScanTile)) {
+    n = (n + kScanTile - 1) / kScanTile;
+    words += 2 * n;    // block sums and their scan
+  }
+  return words + 1;
+}
+
+int scan_u32_ws(const uint32_t* in, uint32_t* out, uint64_t n, uint32_t* total_dev, uint32_t* ws, hipStream_t st) {
+  if (n == 0) {
+    if (total_dev) HM_TRY(fill_u32(total_dev, 0, 1, st));
+    return HM_OK;
+  }
+  const uint64_t nb = (n + kScanTile - 1) / kScanTile;
+  if (nb == 1) {
+    k_scan_tile<uint32_t><<<1, kScanThreads, 0, st>>>(in, out, nullptr, n);
+  } else {
+    uint32_t* sums = ws;
+    uint32_t* sums_scan = ws + nb;
+    k_scan_tile<uint32_t><<<unsigned(nb), kScanThreads, 0, st>>>(in, out, sums, n);
+    HM_HIP(hipGetLastError());
+    HM_TRY(scan_u32_ws(sums, sums_scan, nb, nullptr, ws + 2 * nb, st));
+    k_scan_add<uint32_t><<<unsigned((n + 255) / 256), 256, 0, st>>>(out, sums_scan, n);
+  }
+  HM_HIP(hipGetLastError());
+  if (total_dev) {
+    k_scan_total<uint32_t><<<1, 1, 0, st>>>(in, out, n, total_dev);
+    HM_HIP(hipGetLastError());
+  }
+  return HM_OK;
+}
+
+uint64_t radix_ws_words(uint64_t n) {
+  const uint64_t nb = (n + kSortTile - 1) / kSortTile;
+  return 2 * 256 * nb + scan_ws_words(256 * nb) + 16;
+}
+
+int radix_sort_ws(unsigned long long* keys, uint32_t* vals, unsigned long long* keys_tmp, uint32_t* vals_tmp,
+                  uint64_t n, int bits, uint32_t* ws, hipStream_t st) {
+  if (n <= 1 || bits <= 0) return HM_OK;
+  if (bits > 64) bits = 64;
+  const uint64_t nb64 = (n + kSortTile - 1) / kSortTile;
+  if (nb64 > 0xFFFFFFull) {
+    set_error("radix sort of %llu items is too large", (unsigned long long)n);
+    return HM_EUNSUPPORTED;
+  }
+  const uint32_t nb = uint32_t(nb64);
+  uint32_t* hist = ws;
+  uint32_t* offs = ws + size_t(256) * nb;
+  uint32_t* scan_ws = ws + size_t(512) * nb;
+  unsigned long long* src_k = keys;
+  uint32_t* src_v = vals;
+  unsigned long long* dst_k = keys_tmp;
+  uint32_t* dst_v = vals_tmp;
+  for (int shift = 0; shift < bits; shift += 8) {
+    const int db = (bits - shift) < 8 ? (bits - shift) : 8;
+    k_sort_hist<<<nb, kSortThreads, 0, st>>>(src_k, n, shift, (1u << db) - 1u, hist, nb);
+    HM_HIP(hipGetLastError());
+    HM_TRY(scan_u32_ws(hist, offs, uint64_t(256) * nb, nullptr, scan_ws, st));
+    k_sort_scatter<<<nb, kSortThreads, 0, st>>>(src_k, src_v, dst_k, dst_v, n, shift, db, offs, nb);
+    HM_HIP(hipGetLastError());
+    std::swap(src_k, dst_k);
+    std::swap(src_v, dst_v);
+  }
+  if (src_k != keys) {
+    const unsigned g = unsigned(std::min<uint64_t>((n + 255) / 256, 16384));
+    k_copy<unsigned long long><<<g, 256, 0, st>>>(src_k, keys, n);
+    k_copy<uint32_t><<<g, 256, 0, st>>>(src_v, vals, n);
+    HM_HIP(hipGetLastError());
+  }
+  return HM_OK;
+}
+
+int copy_u32(const uint32_t* src, uint32_t* dst, uint64_t n, hipStream_t st) {
+  if (!n) return HM_OK;
+  k_copy<uint32_t><<<unsigned(std::min<uint64_t>((n + 255) / 256, 16384)), 256, 0, st>>>(src, dst, n);
+  HM_HIP(hipGetLastError());
+  return HM_OK;
+}
+
+int copy_u64(const unsigned long long* src, unsigned long long* dst, uint64_t n, hipStream_t st) {
+  if (!n) return HM_OK;
+  k_copy<unsigned long long><<<unsigned(std::min<uint64_t>((n + 255) / 256, 16384)), 256, 0, st>>>(src, dst, n);
+  HM_HIP(hipGetLastError());
+  return HM_OK;
+}
 
 int scan_exclusive_u32(const uint32_t* in, uint32_t* out, uint64_t n, uint32_t* total_dev, hipStream_t st) {
   HM_TRY(scan_impl<uint32_t>(in, out, n, st));

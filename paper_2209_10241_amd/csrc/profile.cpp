@@ -49,10 +49,14 @@ int drain_locked() {
 
 }  // namespace
 
-bool profiling() { return g_on; }
+thread_local int g_capturing = 0;
+
+bool profiling() { return g_on && !g_capturing; }
+void capture_begin() { ++g_capturing; }
+void capture_end() { --g_capturing; }
 
 ProfileScope::ProfileScope(const char* name, hipStream_t st) : name_(name), st_(st) {
-  if (!g_on) return;
+  if (!profiling()) return;
   if (hipEventCreate(&start_) != hipSuccess || hipEventCreate(&stop_) != hipSuccess) return;
   if (hipEventRecord(start_, st_) != hipSuccess) return;
   active_ = true;

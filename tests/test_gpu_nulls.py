@@ -98,3 +98,43 @@ def test_bad_arguments(hm):
             hm.count_nulls(g, 4, 1, 0)
         with pytest.raises(hm.HMError):
             hm.count_nulls(g, 5, 4, 0)
+
+
+def test_replay_new_seed_and_rebuild(hm):
+    """The captured pipeline replays with a new seed; a different number of
+    copies rebuilds it; both against the oracle."""
+    h = W.random_small(5300, 35, 220, {2: 0.5, 3: 0.35, 4: 0.15})
+    with hm.hm_graph_create(h.members, h.offsets, h.n_nodes) as g:
+        for R, seed in ((6, 10), (6, 11), (9, 12), (6, 13)):
+            _, nl, _ = hm.count_nulls(g, 4, R, seed)
+            nl = nl.cpu().numpy()
+            for c in (0, R - 1):
+                want = core.count_exact(W.Hypergraph(h.n_nodes, *nulls.stub_matching(h, seed, c)), 4)
+                assert np.array_equal(nl[c], want), (R, seed, c)
+        sizes = hm.hm_null_tile_sizes(g)
+        assert len(sizes) == 3 and min(sizes) >= 1
+
+
+@pytest.mark.parametrize("bit_rows", [True, False], ids=["bits", "hash"])
+def test_batched_paths_match_oracle(hm, bit_rows):
+    h = W.random_small(5400, 45, 300, {2: 0.45, 3: 0.35, 4: 0.2})
+    hm.hm_set_option(hm.HM_OPT_BITSET_MAX_NODES, 8192 if bit_rows else 0)
+    try:
+        g = hm.hm_graph_create(h.members, h.offsets, h.n_nodes)
+    finally:
+        hm.hm_set_option(hm.HM_OPT_BITSET_MAX_NODES, 8192)
+    with g:
+        for k in (3, 4):
+            real, nl, _ = hm.count_nulls(g, k, 5, 99)
+            assert np.array_equal(real.cpu().numpy(), core.count_exact(h, k))
+            nl = nl.cpu().numpy()
+            for c in range(5):
+                want = core.count_exact(W.Hypergraph(h.n_nodes, *nulls.stub_matching(h, 99, c)), k)
+                assert np.array_equal(nl[c], want), (k, c)
+
+
+def test_empty_hypergraph(hm):
+    h = W.from_lists([[0], [1]], 3)
+    with hm.hm_graph_create(h.members, h.offsets, h.n_nodes) as g:
+        real, nl, z = hm.count_nulls(g, 4, 3, 1)
+        assert real.sum().item() == 0 and nl.sum().item() == 0 and float(z.abs().sum()) == 0.0
