@@ -113,6 +113,37 @@ def main() -> int:
     hm.hm_profile_enable(False)
     stats = g.stats()
     e2, e3 = g.export(2), g.export(3)
+    exact = counts.cpu().numpy().astype(np.float64)
+
+    # sampled counting (Algorithm 4): time per call and mean relative error
+    # over 32 seeds at 1%, 5%, 10% of every stratum
+    sampled = {}
+    for f in (0.01, 0.05, 0.10):
+        runs = []
+        start.record(stream)
+        for seed in range(32):
+            est, _ = hm.count_sampled(g, 4, f, 1000 + seed, stream=stream)
+            runs.append(est)
+        stop.record(stream)
+        torch.cuda.synchronize()
+        ms = start.elapsed_time(stop) / 32
+        r = torch.stack(runs).double().cpu().numpy()
+        mre = float(np.mean(np.abs(r - exact).sum(axis=1) / exact.sum()))
+        sampled[f"{f:g}"] = {"ms": ms, "mre": mre, "speedup_vs_exact_count": count_ms / ms}
+    ok = [k for k, v in sampled.items() if v["mre"] <= 0.02]
+    best = min(ok, key=lambda k: float(k)) if ok else None
+
+    # batched null model: 64 stub-matched copies counted at k = 4 in one graph launch
+    t0 = time.perf_counter()
+    hm.count_nulls(g, 4, 64, 1, stream=stream)
+    first_ms = (time.perf_counter() - t0) * 1e3
+    reps = 5
+    t0 = time.perf_counter()
+    for i in range(reps):
+        hm.count_nulls(g, 4, 64, 2 + i, stream=stream)
+    null_ms = (time.perf_counter() - t0) * 1e3 / reps
+    nulls = {"copies": 64, "ms_per_batch": null_ms, "ms_per_copy": null_ms / 64,
+             "first_call_ms_incl_tuning_and_capture": first_ms, "tile_sizes": hm.hm_null_tile_sizes(g)}
     g.close()
     words = (h.n_nodes + 31) // 32
     units = _unit_counts(e2, e3, h.n_nodes, words)
@@ -164,6 +195,10 @@ def main() -> int:
                    "connected_4_sets": total},
         "count_only_ms": count_ms,
         "ingest_ms": ms_per_step - count_ms,
+        "sampled": sampled,
+        "sampled_speedup_at_2pct": ({"fraction": float(best), "speedup": sampled[best]["speedup_vs_exact_count"]}
+                                    if best else None),
+        "nulls": nulls,
         "kernels": kernels,
         "units": units,
         "roofline": roof,
