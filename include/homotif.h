@@ -202,6 +202,74 @@ int hm_null_tile_sizes(const hm_graph* H, uint32_t* out3);
  * Synchronous. */
 int hm_null_export(const hm_graph* H, uint64_t seed, uint32_t copy, uint32_t* members, uint64_t* offsets);
 
+/* ---------------------------------------------------------------- learned proposal */
+
+/* Algorithm 4 draws uniformly inside each stratum; any proposal p_e > 0 keeps
+ * the estimate unbiased when each draw of stratum j weighs 1 / (S_j p_e)
+ * (Hansen-Hurwitz; with p_e = 1/|E_j| this is Algorithm 4's correction).  The
+ * learned proposal scores hyperedges with an MLP (16 features -> 64 -> 64 ->
+ * 1, ReLU; bf16 weights and activations on MFMA, fp32 accumulation) trained on
+ * exact per-hyperedge contributions y_e = sum_m raw_e[m] / countmax_m
+ * (Algorithm 4's count for the single sample e), computed by the library on a
+ * (sub)hypergraph.  Parameters (5313 floats): W1[64][16], b1[64],
+ * W2[64][64], b2[64], w3[64], b3. */
+typedef struct hm_model hm_model;
+
+typedef struct {
+  int epochs;      /* passes over the training rows */
+  int batch;       /* rows per Adam step (>= 16) */
+  float lr;        /* Adam learning rate */
+  float gamma;     /* proposal q_e = (1 + predicted y_e)^gamma */
+  float epsilon;   /* mixture weight of the uniform proposal, in (0, 1] */
+  uint64_t seed;   /* initial weights and row order */
+} hm_train_opts;
+
+/* Standardised features of every hyperedge of size 2..k (device float
+ * [n_rows][16], rows: the strata of size 2, 3, 4 in stratum order). */
+int hm_features(const hm_graph* H, int k, float* x, void* stream);
+
+/* Exact per-hyperedge contributions y_e (device double [n_rows], same rows);
+ * the y_e of stratum j sum to the exact total of the classes with maxcard j.
+ * Synchronous. */
+int hm_contrib(const hm_graph* H, int k, double* y, void* stream);
+
+/* MLP forward over n rows of 16 features (device pointers). */
+int hm_mlp_forward(const float* params, const float* x, uint64_t n, float* out, void* stream);
+
+/* Gradient of the mean squared error (device grad[5314]: 5313 parameter
+ * gradients, then the loss) for n rows with targets t.  Synchronous. */
+int hm_mlp_grad(const float* params, const float* x, const float* t, uint64_t n, float* grad, void* stream);
+
+/* Train a proposal on H (usually a subsampled hypergraph): contributions,
+ * features, per-stratum standardised targets log(1 + y_e), Adam on the GPU.
+ * Synchronous. */
+int hm_model_train(const hm_graph* H, int k, const hm_train_opts* opts, hm_model** out);
+int hm_model_destroy(hm_model* M);
+/* Host copy of the 5313 parameters. */
+int hm_model_params(const hm_model* M, float* params_out);
+/* Mean training loss per epoch (host array); returns the number of epochs. */
+int hm_model_loss(const hm_model* M, int max_epochs, float* loss_out);
+
+/* Proposal probabilities of every hyperedge of size 2..k of H under model M
+ * (device double [n_rows]).  Synchronous. */
+int hm_proposal_probs(const hm_graph* H, const hm_model* M, int k, double* p, void* stream);
+
+/* Sampled counts with the learned proposal: S_j = ceil(fraction |E_j|)
+ * draws per stratum with probabilities hm_proposal_probs; draw i of stratum j
+ * is the first hyperedge whose cumulative probability exceeds u * total,
+ * u = (word0 >> 11) 2^-53 of Philox4x64-10 at counter (i, 0, 0, 0) under key
+ * (seed, (3 << 32) | j); est_m = sum over draws of raw[m] / (S_j p_e
+ * countmax_m), fp64 rounded to fp32.  raw (optional): unweighted raw counts.
+ * Synchronous. */
+int count_sampled_learned(const hm_graph* H, const hm_model* M, int k, double fraction, uint64_t seed, float* est,
+                          int64_t* raw, void* stream);
+
+/* The Hansen-Hurwitz estimate on explicit draws: per stratum, device uint32
+ * indices and device double probabilities p of each draw.  Synchronous. */
+int count_sampled_weighted_indices(const hm_graph* H, int k, const uint32_t* idx2, const double* p2, uint64_t s2,
+                                   const uint32_t* idx3, const double* p3, uint64_t s3, const uint32_t* idx4,
+                                   const double* p4, uint64_t s4, float* est, int64_t* raw, void* stream);
+
 /* ---------------------------------------------------------------- options */
 
 /* Process-wide tuning options (read when a graph is created).

@@ -3,6 +3,8 @@ order 3 and 4 on AMD MI355X, behind the C ABI of include/homotif.h."""
 from .binding import (  # noqa: F401
     HM_ALLOC_PAPER, HM_ALLOC_PROPORTIONAL, HM_OPT_BITSET_MAX_NODES, count_nulls, count_sampled, count_sampled_indices,
     hm_null_export, hm_null_tile_sizes,
+    Model, count_sampled_learned, count_sampled_weighted_indices, hm_contrib, hm_features, hm_mlp_forward,
+    hm_mlp_grad, hm_model_train, hm_proposal_probs,
     hm_get_option, hm_sample_draw, hm_sample_sizes, hm_set_option,
     Graph, HMError, LibraryMissing, count_exact, hm_class_info, hm_graph_create, hm_num_classes,
     hm_pattern_class, hm_profile_enable, hm_profile_read, hm_profile_reset, hm_version, lib,

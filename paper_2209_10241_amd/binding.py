@@ -68,6 +68,18 @@ SIGNATURES = {
     "count_nulls": (_int, [_vp, _int, _int, _u64, _vp, _vp, _vp, _vp]),
     "hm_null_export": (_int, [_vp, _u64, _u32, _vp, _vp]),
     "hm_null_tile_sizes": (_int, [_vp, _vp]),
+    "hm_features": (_int, [_vp, _int, _vp, _vp]),
+    "hm_contrib": (_int, [_vp, _int, _vp, _vp]),
+    "hm_mlp_forward": (_int, [_vp, _vp, _u64, _vp, _vp]),
+    "hm_mlp_grad": (_int, [_vp, _vp, _vp, _u64, _vp, _vp]),
+    "hm_model_train": (_int, [_vp, _int, _vp, _vp]),
+    "hm_model_destroy": (_int, [_vp]),
+    "hm_model_params": (_int, [_vp, _vp]),
+    "hm_model_loss": (_int, [_vp, _int, _vp]),
+    "hm_proposal_probs": (_int, [_vp, _vp, _int, _vp, _vp]),
+    "count_sampled_learned": (_int, [_vp, _vp, _int, _dbl, _u64, _vp, _vp, _vp]),
+    "count_sampled_weighted_indices": (_int, [_vp, _int, _vp, _vp, _u64, _vp, _vp, _u64, _vp, _vp, _u64, _vp, _vp,
+                                              _vp]),
     "hm_set_option": (_int, [_int, ctypes.c_int64]),
     "hm_get_option": (_int, [_int, _vp]),
     "hm_profile_enable": (_int, [_int]),
@@ -331,3 +343,137 @@ def hm_null_tile_sizes(H: Graph):
     out = (ctypes.c_uint32 * 3)()
     _check(lib().hm_null_tile_sizes(H.handle, out))
     return [int(x) for x in out]
+
+
+N_PARAMS = 5313
+
+
+class TrainOpts(ctypes.Structure):
+    _fields_ = [("epochs", ctypes.c_int), ("batch", ctypes.c_int), ("lr", ctypes.c_float),
+                ("gamma", ctypes.c_float), ("epsilon", ctypes.c_float), ("seed", ctypes.c_uint64)]
+
+
+def _rows(H: Graph, k: int) -> int:
+    st = H.stats()
+    return st["n2"] + st["n3"] + (st["n4"] if k == 4 else 0)
+
+
+def hm_features(H: Graph, k: int, stream=None):
+    import torch
+    x = torch.empty((_rows(H, k), 16), dtype=torch.float32, device="cuda")
+    _check(lib().hm_features(H.handle, k, _ptr(x), _stream_ptr(stream)))
+    return x
+
+
+def hm_contrib(H: Graph, k: int, stream=None):
+    import torch
+    y = torch.empty(_rows(H, k), dtype=torch.float64, device="cuda")
+    _check(lib().hm_contrib(H.handle, k, _ptr(y), _stream_ptr(stream)))
+    return y
+
+
+def hm_mlp_forward(params, x, stream=None):
+    import torch
+    params = params.to(device="cuda", dtype=torch.float32).contiguous()
+    x = x.to(device="cuda", dtype=torch.float32).contiguous()
+    out = torch.empty(x.shape[0], dtype=torch.float32, device="cuda")
+    _check(lib().hm_mlp_forward(_ptr(params), _ptr(x), x.shape[0], _ptr(out), _stream_ptr(stream)))
+    return out
+
+
+def hm_mlp_grad(params, x, t, stream=None):
+    """(gradient [5313], loss) of the mean squared error."""
+    import torch
+    params = params.to(device="cuda", dtype=torch.float32).contiguous()
+    x = x.to(device="cuda", dtype=torch.float32).contiguous()
+    t = t.to(device="cuda", dtype=torch.float32).contiguous()
+    g = torch.empty(N_PARAMS + 1, dtype=torch.float32, device="cuda")
+    _check(lib().hm_mlp_grad(_ptr(params), _ptr(x), _ptr(t), x.shape[0], _ptr(g), _stream_ptr(stream)))
+    return g[:N_PARAMS], float(g[N_PARAMS].item())
+
+
+class Model:
+    """Owner of an ``hm_model`` handle (a trained proposal)."""
+
+    def __init__(self, handle: int):
+        self._h = ctypes.c_void_p(handle)
+
+    @property
+    def handle(self):
+        if self._h is None or not self._h.value:
+            raise HMError(HM_EINVAL, "model handle already destroyed")
+        return self._h
+
+    def params(self) -> np.ndarray:
+        out = np.zeros(N_PARAMS, dtype=np.float32)
+        _check(lib().hm_model_params(self.handle, out.ctypes.data_as(ctypes.c_void_p)))
+        return out
+
+    def loss(self) -> np.ndarray:
+        n = _check(lib().hm_model_loss(self.handle, 0, None))
+        out = np.zeros(max(n, 1), dtype=np.float32)
+        _check(lib().hm_model_loss(self.handle, n, out.ctypes.data_as(ctypes.c_void_p)))
+        return out[:n]
+
+    def close(self):
+        if self._h is not None and self._h.value and _lib is not None:
+            _lib.hm_model_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+def hm_model_train(H: Graph, k: int, epochs: int = 30, batch: int = 4096, lr: float = 3e-3, gamma: float = 0.5,
+                   epsilon: float = 0.1, seed: int = 0) -> Model:
+    opts = TrainOpts(epochs, batch, lr, gamma, epsilon, int(seed) & (2**64 - 1))
+    out = ctypes.c_void_p()
+    _check(lib().hm_model_train(H.handle, k, ctypes.byref(opts), ctypes.byref(out)))
+    return Model(out.value)
+
+
+def hm_proposal_probs(H: Graph, M: Model, k: int, stream=None):
+    import torch
+    p = torch.empty(_rows(H, k), dtype=torch.float64, device="cuda")
+    _check(lib().hm_proposal_probs(H.handle, M.handle, k, _ptr(p), _stream_ptr(stream)))
+    return p
+
+
+def count_sampled_learned(H: Graph, M: Model, k: int, fraction: float, seed: int, stream=None):
+    import torch
+    n = hm_num_classes(k)
+    est = torch.empty(n, dtype=torch.float32, device="cuda")
+    raw = torch.empty(n, dtype=torch.int64, device="cuda")
+    _check(lib().count_sampled_learned(H.handle, M.handle, k, float(fraction), int(seed) & (2**64 - 1), _ptr(est),
+                                       _ptr(raw), _stream_ptr(stream)))
+    return est, raw
+
+
+def count_sampled_weighted_indices(H: Graph, k: int, samples: dict, probs: dict, stream=None):
+    """Hansen-Hurwitz estimate: samples {j: indices}, probs {j: probability of each draw}."""
+    import torch
+    n = hm_num_classes(k)
+    est = torch.empty(n, dtype=torch.float32, device="cuda")
+    raw = torch.empty(n, dtype=torch.int64, device="cuda")
+    idx, pr, size = {}, {}, {}
+    for j in (2, 3, 4):
+        if samples.get(j) is None or len(samples[j]) == 0:
+            idx[j] = pr[j] = None
+            size[j] = 0
+            continue
+        idx[j] = torch.as_tensor(np.asarray(samples[j]), dtype=torch.int32).cuda().contiguous()
+        pr[j] = torch.as_tensor(np.asarray(probs[j]), dtype=torch.float64).cuda().contiguous()
+        size[j] = idx[j].numel()
+    _check(lib().count_sampled_weighted_indices(H.handle, k, _ptr(idx[2]), _ptr(pr[2]), size[2], _ptr(idx[3]),
+                                                _ptr(pr[3]), size[3], _ptr(idx[4]), _ptr(pr[4]), size[4], _ptr(est),
+                                                _ptr(raw), _stream_ptr(stream)))
+    return est, raw

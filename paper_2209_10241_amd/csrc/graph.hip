@@ -536,6 +536,8 @@ void release(hm_graph* H) {
   dfree(H->sample_idx);
   if (H->null_plan) destroy_null_plan(H->null_plan);
   H->null_plan = nullptr;
+  if (H->proposal) destroy_proposal_cache(H->proposal);
+  H->proposal = nullptr;
 }
 
 }  // namespace

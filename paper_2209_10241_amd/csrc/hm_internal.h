@@ -177,6 +177,8 @@ void dfree(void* p);
 
 struct NullPlan;
 void destroy_null_plan(NullPlan* p);
+struct ProposalCache;
+void destroy_proposal_cache(ProposalCache* c);
 
 }  // namespace hm
 
@@ -224,4 +226,6 @@ struct hm_graph {
   uint64_t sample_cap = 0;
   // buffers and captured HIP graph of the batched null-model pipeline
   hm::NullPlan* null_plan = nullptr;
+  // learned-proposal probabilities of the last model used with this graph
+  hm::ProposalCache* proposal = nullptr;
 };

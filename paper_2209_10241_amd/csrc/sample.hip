@@ -35,15 +35,17 @@ __global__ void __launch_bounds__(kThreads) k_sample_j4(const uint32_t* __restri
                                                         const uint32_t* __restrict__ e4, uint64_t n4, Set64 hs2,
                                                         Set128 hs3, const uint32_t* __restrict__ bits, uint32_t W,
                                                         const uint8_t* __restrict__ lut_g,
-                                                        unsigned long long* __restrict__ hist) {
+                                                        unsigned long long* __restrict__ hist,
+                                                        unsigned long long* __restrict__ ps) {
   __shared__ uint8_t lut[2048];
-  __shared__ unsigned long long h[256];
+  __shared__ unsigned long long h_lds[256];
   load_lut(lut, lut_g, 2048);
-  h[threadIdx.x] = 0;
+  h_lds[threadIdx.x] = 0;
   __syncthreads();
   for (uint64_t s = uint64_t(blockIdx.x) * kThreads + threadIdx.x; s < S; s += uint64_t(gridDim.x) * kThreads) {
     const uint64_t i = idx[s];
     if (i >= n4) continue;
+    unsigned long long* h = ps ? ps + s * 256 : h_lds;
     const uint32_t a = e4[4 * i], b = e4[4 * i + 1], c = e4[4 * i + 2], d = e4[4 * i + 3];
     uint32_t p = 1u << 10;
     p |= pair_bit(hs2, bits, W, a, b) << 0;
@@ -59,7 +61,7 @@ __global__ void __launch_bounds__(kThreads) k_sample_j4(const uint32_t* __restri
     atomicAdd(&h[lut[p]], 1ull);
   }
   __syncthreads();
-  flush(h, hist + kRaw, 256);
+  flush(h_lds, hist + kRaw, 256);
 }
 
 // j = 3 at order 4: the neighbourhood of the sampled 3-node hyperedge.
@@ -67,7 +69,8 @@ __global__ void __launch_bounds__(kThreads) k_sample_j3_bits(
     const uint32_t* __restrict__ idx, uint64_t S, const uint32_t* __restrict__ e3, uint64_t n3,
     const uint32_t* __restrict__ e4, const uint32_t* __restrict__ i3_off, const uint32_t* __restrict__ i3_idx,
     const uint32_t* __restrict__ i4_off, const uint32_t* __restrict__ i4_idx, const uint32_t* __restrict__ bits,
-    uint32_t W, const uint8_t* __restrict__ lut_g, unsigned long long* __restrict__ hist) {
+    uint32_t W, const uint8_t* __restrict__ lut_g, unsigned long long* __restrict__ hist,
+    unsigned long long* __restrict__ ps) {
   __shared__ uint8_t lut[2048];
   __shared__ unsigned long long h[256];
   __shared__ B4Scratch scratch[kWavesPerBlock];
@@ -81,7 +84,7 @@ __global__ void __launch_bounds__(kThreads) k_sample_j3_bits(
     const uint64_t i = idx[s];
     if (i >= n3) continue;
     b4_edge_bits<false>(e3[3 * i], e3[3 * i + 1], e3[3 * i + 2], e3, e4, i3_off, i3_idx, i4_off, i4_idx, bits, W,
-                        scratch[wv], lut, h, nullptr);
+                        scratch[wv], lut, ps ? ps + s * 256 : h, nullptr);
   }
   __syncthreads();
   flush(h, hist + kRaw, 256);
@@ -91,7 +94,7 @@ __global__ void __launch_bounds__(kThreads) k_sample_j3_hash(
     const uint32_t* __restrict__ idx, uint64_t S, const uint32_t* __restrict__ e3, uint64_t n3,
     const uint32_t* __restrict__ g2_off, const uint32_t* __restrict__ g2_adj, const uint32_t* __restrict__ i3_off,
     const uint32_t* __restrict__ i3_idx, Set64 hs2, Set128 hs3, Set128 hs4, const uint8_t* __restrict__ lut_g,
-    unsigned long long* __restrict__ hist) {
+    unsigned long long* __restrict__ hist, unsigned long long* __restrict__ ps) {
   __shared__ uint8_t lut[2048];
   __shared__ unsigned long long h[256];
   load_lut(lut, lut_g, 2048);
@@ -103,7 +106,7 @@ __global__ void __launch_bounds__(kThreads) k_sample_j3_hash(
     const uint64_t i = idx[s];
     if (i >= n3) continue;
     b4_edge_hash<false>(e3[3 * i], e3[3 * i + 1], e3[3 * i + 2], e3, g2_off, g2_adj, i3_off, i3_idx, hs2, hs3, hs4,
-                        lut, h, nullptr);
+                        lut, ps ? ps + s * 256 : h, nullptr);
   }
   __syncthreads();
   flush(h, hist + kRaw, 256);
@@ -169,15 +172,16 @@ __global__ void __launch_bounds__(kThreads) k_sample_j2_k4(
     const uint32_t* __restrict__ idx, uint64_t S, const uint32_t* __restrict__ e2, uint64_t n2,
     const uint32_t* __restrict__ g2_off, const uint32_t* __restrict__ g2_adj, Set64 hs2, Set128 hs3, Set128 hs4,
     const uint32_t* __restrict__ bits, uint32_t W, const uint8_t* __restrict__ lut_g,
-    unsigned long long* __restrict__ hist) {
+    unsigned long long* __restrict__ hist, unsigned long long* __restrict__ ps) {
   __shared__ uint8_t lut[2048];
-  __shared__ unsigned long long h[256];
+  __shared__ unsigned long long h_lds[256];
   load_lut(lut, lut_g, 2048);
-  h[threadIdx.x] = 0;
+  h_lds[threadIdx.x] = 0;
   __syncthreads();
   for (uint64_t s = blockIdx.x; s < S; s += gridDim.x) {
     const uint64_t i = idx[s];
     if (i >= n2) continue;
+    unsigned long long* h = ps ? ps + s * 256 : h_lds;
     const uint32_t u = e2[2 * i], w = e2[2 * i + 1];
     const uint32_t ub = g2_off[u], du = g2_off[u + 1] - ub;
     const uint32_t wb = g2_off[w], dw = g2_off[w + 1] - wb;
@@ -207,7 +211,7 @@ __global__ void __launch_bounds__(kThreads) k_sample_j2_k4(
     }
   }
   __syncthreads();
-  flush(h, hist + kRaw, 256);
+  flush(h_lds, hist + kRaw, 256);
 }
 
 // order 3, j = 3: the sampled 3-node hyperedge with its pairs
@@ -215,22 +219,24 @@ __global__ void __launch_bounds__(kThreads) k_sample_j3_k3(const uint32_t* __res
                                                            const uint32_t* __restrict__ e3, uint64_t n3, Set64 hs2,
                                                            const uint32_t* __restrict__ bits, uint32_t W,
                                                            const uint8_t* __restrict__ lut_g,
-                                                           unsigned long long* __restrict__ hist) {
+                                                           unsigned long long* __restrict__ hist,
+                                                           unsigned long long* __restrict__ ps) {
   __shared__ uint8_t lut[16];
-  __shared__ unsigned long long h[256];
+  __shared__ unsigned long long h_lds[256];
   load_lut(lut, lut_g, 16);
-  h[threadIdx.x] = 0;
+  h_lds[threadIdx.x] = 0;
   __syncthreads();
   for (uint64_t s = uint64_t(blockIdx.x) * kThreads + threadIdx.x; s < S; s += uint64_t(gridDim.x) * kThreads) {
     const uint64_t i = idx[s];
     if (i >= n3) continue;
+    unsigned long long* h = ps ? ps + s * 256 : h_lds;
     const uint32_t a = e3[3 * i], b = e3[3 * i + 1], c = e3[3 * i + 2];
     const uint32_t p = (1u << 3) | pair_bit(hs2, bits, W, a, b) | (pair_bit(hs2, bits, W, a, c) << 1) |
                        (pair_bit(hs2, bits, W, b, c) << 2);
     atomicAdd(&h[lut[p]], 1ull);
   }
   __syncthreads();
-  flush(h, hist + kRaw, 256);
+  flush(h_lds, hist + kRaw, 256);
 }
 
 // order 3, j = 2: the sampled pair {u, w} and one neighbour x of u or w
@@ -242,11 +248,12 @@ __global__ void __launch_bounds__(kThreads) k_sample_j2_k3(const uint32_t* __res
                                                            const uint32_t* __restrict__ g2_adj, Set64 hs2,
                                                            Set128 hs3, const uint32_t* __restrict__ bits, uint32_t W,
                                                            const uint8_t* __restrict__ lut_g,
-                                                           unsigned long long* __restrict__ hist) {
+                                                           unsigned long long* __restrict__ hist,
+                                                           unsigned long long* __restrict__ ps) {
   __shared__ uint8_t lut[16];
-  __shared__ unsigned long long h[256];
+  __shared__ unsigned long long h_lds[256];
   load_lut(lut, lut_g, 16);
-  h[threadIdx.x] = 0;
+  h_lds[threadIdx.x] = 0;
   __syncthreads();
   const int lane = threadIdx.x & (kWave - 1);
   const uint64_t wave = uint64_t(blockIdx.x) * kWavesPerBlock + threadIdx.x / kWave;
@@ -257,6 +264,7 @@ __global__ void __launch_bounds__(kThreads) k_sample_j2_k3(const uint32_t* __res
     const uint32_t u = e2[2 * i], w = e2[2 * i + 1];
     const uint32_t ub = g2_off[u], du = g2_off[u + 1] - ub;
     const uint32_t wb = g2_off[w], dw = g2_off[w + 1] - wb;
+    unsigned long long* h = ps ? ps + s * 256 : h_lds;
     for (uint32_t p = lane; p < du + dw; p += kWave) {
       const uint32_t x = nodeL(g2_adj, ub, du, wb, p);
       if (x == u || x == w) continue;
@@ -271,7 +279,7 @@ __global__ void __launch_bounds__(kThreads) k_sample_j2_k3(const uint32_t* __res
     }
   }
   __syncthreads();
-  flush(h, hist + kRaw, 256);
+  flush(h_lds, hist + kRaw, 256);
 }
 
 struct ScaleArgs {
@@ -348,52 +356,63 @@ int sample_sizes(const hm_graph* H, int k, double fraction, int allocation, uint
   return HM_OK;
 }
 
-// Enumerate around explicit samples (device index arrays) and scale.
-int sampled_from_indices(const hm_graph* H, int k, const uint32_t* const idx[5], const uint64_t S[5], float* est,
-                         int64_t* raw, hipStream_t st) {
+// Enumerate around explicit samples (device index arrays).  With ps == null
+// the raw counts go to hm_graph::hist; otherwise sample s of stratum j adds
+// to row ps[row0[j] + s] (256 counters per row, zeroed by the caller).
+int enumerate_samples(const hm_graph* H, int k, const uint32_t* const idx[5], const uint64_t S[5],
+                      unsigned long long* ps, const uint64_t row0[5], hipStream_t st) {
   const uint8_t *lut4 = nullptr, *lut3 = nullptr;
   HM_TRY(device_luts(H->device, &lut4, &lut3));
-  HM_TRY(fill_u64(H->hist, 0, 4 * 256, st));
   const uint64_t n2 = H->n_by_size[2], n3 = H->n_by_size[3], n4 = H->n_by_size[4];
+  auto rows = [&](int j) { return ps ? ps + row0[j] * 256 : nullptr; };
   if (k == 4) {
     if (S[4]) {
-      ProfileScope ps("k_sample_j4", st);
+      ProfileScope pscope("k_sample_j4", st);
       k_sample_j4<<<grid_for(S[4], kThreads), kThreads, 0, st>>>(idx[4], S[4], H->e4, n4, H->hs2, H->hs3, H->bits,
-                                                                  H->words, lut4, H->hist);
+                                                                  H->words, lut4, H->hist, rows(4));
     }
     if (S[3]) {
       if (H->bits) {
-        ProfileScope ps("k_sample_j3_bits", st);
+        ProfileScope pscope("k_sample_j3_bits", st);
         k_sample_j3_bits<<<grid_for(S[3], kWavesPerBlock), kThreads, 0, st>>>(
             idx[3], S[3], H->e3, n3, H->e4, H->i3_off, H->i3_idx, H->i4_off, H->i4_idx, H->bits, H->words, lut4,
-            H->hist);
+            H->hist, rows(3));
       } else {
-        ProfileScope ps("k_sample_j3_hash", st);
+        ProfileScope pscope("k_sample_j3_hash", st);
         k_sample_j3_hash<<<grid_for(S[3], kWavesPerBlock), kThreads, 0, st>>>(
             idx[3], S[3], H->e3, n3, H->g2_off, H->g2_adj, H->i3_off, H->i3_idx, H->hs2, H->hs3, H->hs4, lut4,
-            H->hist);
+            H->hist, rows(3));
       }
     }
     if (S[2]) {
-      ProfileScope ps("k_sample_j2_k4", st);
+      ProfileScope pscope("k_sample_j2_k4", st);
       k_sample_j2_k4<<<grid_for(S[2], 1, 1024), kThreads, 0, st>>>(idx[2], S[2], H->e2, n2, H->g2_off, H->g2_adj,
                                                                     H->hs2, H->hs3, H->hs4, H->bits, H->words, lut4,
-                                                                    H->hist);
+                                                                    H->hist, rows(2));
     }
   } else {
     if (S[3]) {
-      ProfileScope ps("k_sample_j3_k3", st);
+      ProfileScope pscope("k_sample_j3_k3", st);
       k_sample_j3_k3<<<grid_for(S[3], kThreads), kThreads, 0, st>>>(idx[3], S[3], H->e3, n3, H->hs2, H->bits,
-                                                                     H->words, lut3, H->hist);
+                                                                     H->words, lut3, H->hist, rows(3));
     }
     if (S[2]) {
-      ProfileScope ps("k_sample_j2_k3", st);
+      ProfileScope pscope("k_sample_j2_k3", st);
       k_sample_j2_k3<<<grid_for(S[2], kWavesPerBlock), kThreads, 0, st>>>(idx[2], S[2], H->e2, n2, H->g2_off,
                                                                           H->g2_adj, H->hs2, H->hs3, H->bits,
-                                                                          H->words, lut3, H->hist);
+                                                                          H->words, lut3, H->hist, rows(2));
     }
   }
   HM_HIP(hipGetLastError());
+  return HM_OK;
+}
+
+// Enumerate around explicit samples and scale (Algorithm 4).
+int sampled_from_indices(const hm_graph* H, int k, const uint32_t* const idx[5], const uint64_t S[5], float* est,
+                         int64_t* raw, hipStream_t st) {
+  HM_TRY(fill_u64(H->hist, 0, 4 * 256, st));
+  const uint64_t row0[5] = {0, 0, 0, 0, 0};
+  HM_TRY(enumerate_samples(H, k, idx, S, nullptr, row0, st));
   const ClassTables& t = class_tables();
   ScaleArgs a;
   for (int j = 0; j < 5; ++j) {

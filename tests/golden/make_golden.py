@@ -28,6 +28,12 @@ def main():
         out["cases"].append({"workload": name, "seed": 0, "k": k, "counts": c.tolist(),
                              "oracle_seconds": round(time.time() - t0, 2)})
         print(name, k, int(c.sum()), f"{time.time() - t0:.1f}s", flush=True)
+    h = W.scaled_communication(0.004, seed=0)
+    t0 = time.time()
+    c = core.count_exact(h, 4)
+    out["cases"].append({"workload": "communication_scaled_0.004", "seed": 0, "k": 4, "counts": c.tolist(),
+                         "oracle_seconds": round(time.time() - t0, 2)})
+    print("communication_scaled_0.004", int(c.sum()), flush=True)
     # null copies of the order-4 workload (stub matching, seed 1): a few copies
     h = W.cfg1_facetoface_k4(0)
     for copy in (0, 1, 63):
