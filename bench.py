@@ -23,6 +23,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "order-4 motif count time per hypergraph; sampled speedup at ≤2% mean rel err"
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_exact_k4_facetoface_N400_E30000.md")
+# sources the exact counting kernels are compiled from: HBM traffic measured with
+# hardware counters is only reported while these are unchanged
+EXACT_SOURCES = ("exact.hip", "hm_items.h", "hm_b4.h", "hm_device.h", "hm_internal.h")
 HBM_PEAK_GBS = 8000.0
 # integer VALU issue rate: 256 CUs x 64 lanes per cycle x 2.4 GHz
 ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
@@ -53,12 +57,41 @@ def _unit_counts(e2: np.ndarray, e3: np.ndarray, n_nodes: int, words: int) -> di
     return {"c4_word_tasks": int(ys) * words, "b4_candidates": cand}
 
 
+def exact_source_digest() -> str:
+    import hashlib
+    d = hashlib.sha256()
+    for name in EXACT_SOURCES:
+        with open(os.path.join(ROOT, "paper_2209_10241_amd", "csrc", name), "rb") as f:
+            d.update(f.read())
+    return d.hexdigest()[:16]
+
+
+def measured_traffic() -> dict:
+    """Per-launch HBM bytes (FETCH_SIZE + WRITE_SIZE, copy-calibrated) by kernel, if still current."""
+    try:
+        lines = open(TRAFFIC_FILE).read().splitlines()
+    except OSError:
+        return {}
+    digest = next((l.split("`")[1] for l in lines if l.startswith("source digest:")), None)
+    if digest != exact_source_digest():
+        return {}
+    out = {}
+    for l in lines:
+        cols = [c.strip() for c in l.strip().strip("|").split("|")]
+        if len(cols) == 6 and cols[0].startswith("k_") and cols[5].replace(".", "").isdigit():
+            out[cols[0]] = float(cols[5])
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--exact-only", action="store_true", help="skip the sampled and null-model measurements")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first copy 256 MiB device to device (a kernel of known traffic for counter scaling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the counting path runs on a single MI355X "
@@ -71,6 +104,12 @@ def main() -> int:
 
     torch.cuda.set_device(0)
     dev = torch.device("cuda:0")
+    if args.copy_calibration:
+        src = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     h = W.cfg1_facetoface_k4(0)
     members = torch.from_numpy(h.members.astype(np.int32)).to(dev)
     offsets = torch.from_numpy(h.offsets.astype(np.int64)).to(dev)
@@ -118,7 +157,7 @@ def main() -> int:
     # sampled counting (Algorithm 4): time per call and mean relative error
     # over 32 seeds at 1%, 5%, 10% of every stratum
     sampled = {}
-    for f in (0.01, 0.05, 0.10):
+    for f in (() if args.exact_only else (0.01, 0.05, 0.10)):
         runs = []
         start.record(stream)
         for seed in range(32):
@@ -134,22 +173,25 @@ def main() -> int:
     best = min(ok, key=lambda k: float(k)) if ok else None
 
     # batched null model: 64 stub-matched copies counted at k = 4 in one graph launch
-    t0 = time.perf_counter()
-    hm.count_nulls(g, 4, 64, 1, stream=stream)
-    first_ms = (time.perf_counter() - t0) * 1e3
-    reps = 5
-    t0 = time.perf_counter()
-    for i in range(reps):
-        hm.count_nulls(g, 4, 64, 2 + i, stream=stream)
-    null_ms = (time.perf_counter() - t0) * 1e3 / reps
-    nulls = {"copies": 64, "ms_per_batch": null_ms, "ms_per_copy": null_ms / 64,
-             "first_call_ms_incl_tuning_and_capture": first_ms, "tile_sizes": hm.hm_null_tile_sizes(g)}
+    nulls = None
+    if not args.exact_only:
+        t0 = time.perf_counter()
+        hm.count_nulls(g, 4, 64, 1, stream=stream)
+        first_ms = (time.perf_counter() - t0) * 1e3
+        reps = 5
+        t0 = time.perf_counter()
+        for i in range(reps):
+            hm.count_nulls(g, 4, 64, 2 + i, stream=stream)
+        null_ms = (time.perf_counter() - t0) * 1e3 / reps
+        nulls = {"copies": 64, "ms_per_batch": null_ms, "ms_per_copy": null_ms / 64,
+                 "first_call_ms_incl_tuning_and_capture": first_ms, "tile_sizes": hm.hm_null_tile_sizes(g)}
     g.close()
     words = (h.n_nodes + 31) // 32
     units = _unit_counts(e2, e3, h.n_nodes, words)
     kernels = {k: {"launches": n, "avg_ms": ms / max(n, 1)} for k, (n, ms) in prof.items()}
 
     # roofline of the dominant kernel
+    traffic = measured_traffic()
     dom = max(kernels, key=lambda k: kernels[k]["avg_ms"])
     avg_s = kernels[dom]["avg_ms"] / 1e3
     if dom == "k_case_c4_bits":
@@ -157,13 +199,13 @@ def main() -> int:
         # integer operations on three adjacency words held in cache
         ops = units["c4_word_tasks"] * 24
         roof = {"bound": "alu", "achieved": ops / avg_s / 1e12, "peak": ALU_PEAK_TOPS, "unit": "Tops/s",
-                "frac": ops / avg_s / 1e12 / ALU_PEAK_TOPS, "traffic": None}
+                "frac": ops / avg_s / 1e12 / ALU_PEAK_TOPS, "traffic": traffic.get("k_case_c4_bits")}
     else:
         # per generator instance: a 4-byte adjacency entry, 3 pair keys (8 B) and
         # 3 triple + 1 quadruple keys (16 B) of fill-in
         byts = units["b4_candidates"] * 92
         roof = {"bound": "hbm", "achieved": byts / avg_s / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": byts / avg_s / 1e9 / HBM_PEAK_GBS, "traffic": None}
+                "frac": byts / avg_s / 1e9 / HBM_PEAK_GBS, "traffic": traffic.get("k_case_b4")}
     roof["kernel"] = dom
 
     cpu = None
