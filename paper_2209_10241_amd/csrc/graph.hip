@@ -512,6 +512,8 @@ int build(hm_graph* H, const uint32_t* members_in, const uint64_t* offsets_in, u
     }
   }
   HM_TRY(owned(&H->hist, 4 * 256));
+  HM_TRY(owned(&H->sample_hist, 256 + 8));
+  HM_TRY(fill_u64(H->sample_hist, 0, 256 + 8, st));
   HM_HIP(hipStreamSynchronize(st));
   return HM_OK;
 }
@@ -533,7 +535,7 @@ void release(hm_graph* H) {
   dfree(H->i4_idx);
   dfree(H->bits);
   dfree(H->hist);
-  dfree(H->sample_idx);
+  dfree(H->sample_hist);
   if (H->null_plan) destroy_null_plan(H->null_plan);
   H->null_plan = nullptr;
   if (H->proposal) destroy_proposal_cache(H->proposal);

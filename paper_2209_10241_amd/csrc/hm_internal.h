@@ -221,9 +221,9 @@ struct hm_graph {
 
   // histogram scratch, reused by the counting calls (serialised per graph)
   unsigned long long* hist = nullptr;      // 4 x 256 counters
-  // sample index scratch of the sampled counting calls
-  uint32_t* sample_idx = nullptr;
-  uint64_t sample_cap = 0;
+  // raw counters (256) and finished-workgroup ticket of the sampled counting
+  // calls; zero between calls
+  unsigned long long* sample_hist = nullptr;
   // buffers and captured HIP graph of the batched null-model pipeline
   hm::NullPlan* null_plan = nullptr;
   // learned-proposal probabilities of the last model used with this graph

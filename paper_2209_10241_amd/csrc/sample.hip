@@ -10,7 +10,7 @@
 // with mc = maxcard(m), formed in fp64 and rounded once to fp32.
 #include <cmath>
 
-#include "hm_b4.h"
+#include "hm_items.h"
 
 namespace hm {
 namespace {
@@ -30,86 +30,64 @@ __global__ void k_check_indices(const uint32_t* __restrict__ idx, uint64_t S, ui
     if (idx[i] >= n_j) atomicOr(bad, 1u);
 }
 
-// j = 4: the sampled 4-node hyperedge is the only candidate set.
-__global__ void __launch_bounds__(kThreads) k_sample_j4(const uint32_t* __restrict__ idx, uint64_t S,
-                                                        const uint32_t* __restrict__ e4, uint64_t n4, Set64 hs2,
-                                                        Set128 hs3, const uint32_t* __restrict__ bits, uint32_t W,
-                                                        const uint8_t* __restrict__ lut_g,
-                                                        unsigned long long* __restrict__ hist,
-                                                        unsigned long long* __restrict__ ps) {
-  __shared__ uint8_t lut[2048];
-  __shared__ unsigned long long h_lds[256];
-  load_lut(lut, lut_g, 2048);
-  h_lds[threadIdx.x] = 0;
-  __syncthreads();
-  for (uint64_t s = uint64_t(blockIdx.x) * kThreads + threadIdx.x; s < S; s += uint64_t(gridDim.x) * kThreads) {
-    const uint64_t i = idx[s];
-    if (i >= n4) continue;
-    unsigned long long* h = ps ? ps + s * 256 : h_lds;
-    const uint32_t a = e4[4 * i], b = e4[4 * i + 1], c = e4[4 * i + 2], d = e4[4 * i + 3];
+// Where sample s of stratum j comes from: an explicit index list, or draw s of
+// the stratum's Philox stream (the same words k_draw writes out).
+struct Draws {
+  const uint32_t* idx[5];
+  unsigned long long S[5];
+  unsigned long long n[5];
+  unsigned long long seed;
+  __device__ uint64_t at(int j, uint64_t s) const {
+    if (idx[j]) return idx[j][s];
+    const Philox4 r = philox4x64_10(s, 0, 0, 0, seed, (kDomainSample << 32) | uint64_t(j));
+    return bounded64(r.v[0], n[j]);
+  }
+};
+
+__device__ inline unsigned long long* row_or(unsigned long long* rows, uint64_t s, unsigned long long* h) {
+  return rows ? rows + s * 256 : h;
+}
+
+// j = 4: the sampled 4-node hyperedge is the only candidate set.  One thread
+// per sample.
+__device__ void sample_j4(const View& v, const Draws& d, uint32_t part, uint32_t n_parts, const uint8_t* lut,
+                          unsigned long long* h_lds, unsigned long long* rows) {
+  for (uint64_t s = uint64_t(part) * kThreads + threadIdx.x; s < d.S[4]; s += uint64_t(n_parts) * kThreads) {
+    const uint64_t i = d.at(4, s);
+    if (i >= d.n[4]) continue;
+    const uint32_t a = v.e4[4 * i], b = v.e4[4 * i + 1], c = v.e4[4 * i + 2], e = v.e4[4 * i + 3];
     uint32_t p = 1u << 10;
-    p |= pair_bit(hs2, bits, W, a, b) << 0;
-    p |= pair_bit(hs2, bits, W, a, c) << 1;
-    p |= pair_bit(hs2, bits, W, b, c) << 2;
-    p |= uint32_t(set128_has(hs3, key3(a, b, c))) << 3;
-    p |= pair_bit(hs2, bits, W, a, d) << 4;
-    p |= pair_bit(hs2, bits, W, b, d) << 5;
-    p |= uint32_t(set128_has(hs3, key3(a, b, d))) << 6;
-    p |= pair_bit(hs2, bits, W, c, d) << 7;
-    p |= uint32_t(set128_has(hs3, key3(a, c, d))) << 8;
-    p |= uint32_t(set128_has(hs3, key3(b, c, d))) << 9;
-    atomicAdd(&h[lut[p]], 1ull);
+    p |= pair_bit(v.hs2, v.bits, v.W, a, b) << 0;
+    p |= pair_bit(v.hs2, v.bits, v.W, a, c) << 1;
+    p |= pair_bit(v.hs2, v.bits, v.W, b, c) << 2;
+    p |= uint32_t(set128_has(v.hs3, key3(a, b, c))) << 3;
+    p |= pair_bit(v.hs2, v.bits, v.W, a, e) << 4;
+    p |= pair_bit(v.hs2, v.bits, v.W, b, e) << 5;
+    p |= uint32_t(set128_has(v.hs3, key3(a, b, e))) << 6;
+    p |= pair_bit(v.hs2, v.bits, v.W, c, e) << 7;
+    p |= uint32_t(set128_has(v.hs3, key3(a, c, e))) << 8;
+    p |= uint32_t(set128_has(v.hs3, key3(b, c, e))) << 9;
+    atomicAdd(&row_or(rows, s, h_lds)[lut[p]], 1ull);
   }
-  __syncthreads();
-  flush(h_lds, hist + kRaw, 256);
 }
 
-// j = 3 at order 4: the neighbourhood of the sampled 3-node hyperedge.
-__global__ void __launch_bounds__(kThreads) k_sample_j3_bits(
-    const uint32_t* __restrict__ idx, uint64_t S, const uint32_t* __restrict__ e3, uint64_t n3,
-    const uint32_t* __restrict__ e4, const uint32_t* __restrict__ i3_off, const uint32_t* __restrict__ i3_idx,
-    const uint32_t* __restrict__ i4_off, const uint32_t* __restrict__ i4_idx, const uint32_t* __restrict__ bits,
-    uint32_t W, const uint8_t* __restrict__ lut_g, unsigned long long* __restrict__ hist,
-    unsigned long long* __restrict__ ps) {
-  __shared__ uint8_t lut[2048];
-  __shared__ unsigned long long h[256];
-  __shared__ B4Scratch scratch[kWavesPerBlock];
-  load_lut(lut, lut_g, 2048);
-  h[threadIdx.x] = 0;
-  __syncthreads();
+// j = 3 at order 4: the neighbourhood of the sampled 3-node hyperedge.  One
+// wavefront per sample.
+template <bool BITS>
+__device__ void sample_j3_k4(const View& v, const Draws& d, uint32_t part, uint32_t n_parts, B4Scratch* scratch,
+                             const uint8_t* lut, unsigned long long* h_lds, unsigned long long* rows) {
   const int wv = threadIdx.x / kWave;
-  const uint64_t wave = uint64_t(blockIdx.x) * kWavesPerBlock + wv;
-  const uint64_t n_waves = uint64_t(gridDim.x) * kWavesPerBlock;
-  for (uint64_t s = wave; s < S; s += n_waves) {
-    const uint64_t i = idx[s];
-    if (i >= n3) continue;
-    b4_edge_bits<false>(e3[3 * i], e3[3 * i + 1], e3[3 * i + 2], e3, e4, i3_off, i3_idx, i4_off, i4_idx, bits, W,
-                        scratch[wv], lut, ps ? ps + s * 256 : h, nullptr);
+  for (uint64_t s = uint64_t(part) * kWavesPerBlock + wv; s < d.S[3]; s += uint64_t(n_parts) * kWavesPerBlock) {
+    const uint64_t i = d.at(3, s);
+    if (i >= d.n[3]) continue;
+    const uint32_t a = v.e3[3 * i], b = v.e3[3 * i + 1], c = v.e3[3 * i + 2];
+    if constexpr (BITS)
+      b4_edge_bits<false>(a, b, c, v.e3, v.e4, v.i3_off, v.i3_idx, v.i4_off, v.i4_idx, v.bits, v.W, scratch[wv], lut,
+                          row_or(rows, s, h_lds), nullptr);
+    else
+      b4_edge_hash<false>(a, b, c, v.e3, v.g2_off, v.g2_adj, v.i3_off, v.i3_idx, v.hs2, v.hs3, v.hs4, lut,
+                          row_or(rows, s, h_lds), nullptr);
   }
-  __syncthreads();
-  flush(h, hist + kRaw, 256);
-}
-
-__global__ void __launch_bounds__(kThreads) k_sample_j3_hash(
-    const uint32_t* __restrict__ idx, uint64_t S, const uint32_t* __restrict__ e3, uint64_t n3,
-    const uint32_t* __restrict__ g2_off, const uint32_t* __restrict__ g2_adj, const uint32_t* __restrict__ i3_off,
-    const uint32_t* __restrict__ i3_idx, Set64 hs2, Set128 hs3, Set128 hs4, const uint8_t* __restrict__ lut_g,
-    unsigned long long* __restrict__ hist, unsigned long long* __restrict__ ps) {
-  __shared__ uint8_t lut[2048];
-  __shared__ unsigned long long h[256];
-  load_lut(lut, lut_g, 2048);
-  h[threadIdx.x] = 0;
-  __syncthreads();
-  const uint64_t wave = uint64_t(blockIdx.x) * kWavesPerBlock + threadIdx.x / kWave;
-  const uint64_t n_waves = uint64_t(gridDim.x) * kWavesPerBlock;
-  for (uint64_t s = wave; s < S; s += n_waves) {
-    const uint64_t i = idx[s];
-    if (i >= n3) continue;
-    b4_edge_hash<false>(e3[3 * i], e3[3 * i + 1], e3[3 * i + 2], e3, g2_off, g2_adj, i3_off, i3_idx, hs2, hs3, hs4,
-                        lut, ps ? ps + s * 256 : h, nullptr);
-  }
-  __syncthreads();
-  flush(h, hist + kRaw, 256);
 }
 
 // Row-major index of the pair (p < q) among n items: row p starts at
@@ -126,32 +104,20 @@ __device__ inline void pair_from_index(uint64_t t, uint64_t n, uint32_t& p, uint
   q = uint32_t(t - start(pp) + pp + 1);
 }
 
-// j = 2 at order 4: the sampled pair e = {u, w}; the other two nodes x, y make
-// e u {x, y} connected through pairs (a larger hyperedge would exceed e).
-// L lists the neighbours of u then those of w; a position is valid when its
-// node is neither u nor w and, for w's part, not also a neighbour of u, so A
-// = the valid nodes, each once.  Either both x and y lie in A (a pair of valid
-// positions p < q) or x lies in A and y is a neighbour of x outside A u e.
-// One workgroup per sample.
+// j = 2 at order 4 without bit rows: the sampled pair e = {u, w}; the other
+// two nodes x, y make e u {x, y} connected through pairs (a larger hyperedge
+// would exceed e).  L lists the neighbours of u then those of w; a position
+// is valid when its node is neither u nor w and, for w's part, not also a
+// neighbour of u, so A = the valid nodes, each once.  Either both x and y lie
+// in A (a pair of valid positions p < q) or x lies in A and y is a neighbour
+// of x outside A u e.  One workgroup per sample.
 __device__ inline uint32_t nodeL(const uint32_t* g2_adj, uint32_t ub, uint32_t du, uint32_t wb, uint32_t p) {
   return p < du ? g2_adj[ub + p] : g2_adj[wb + (p - du)];
 }
 
-__device__ inline void j2_candidate(uint32_t u, uint32_t w, uint32_t x, uint32_t y, const Set64& hs2,
-                                    const Set128& hs3, const Set128& hs4, const uint32_t* bits, uint32_t W,
+__device__ inline void j2_candidate(const View& v, uint32_t u, uint32_t w, uint32_t x, uint32_t y,
                                     const uint8_t* lut, unsigned long long* h) {
-  uint32_t t0 = u, t1 = w, t2 = x;
-  sort3(t0, t1, t2);
-  if (set128_has(hs3, key3(t0, t1, t2))) return;
-  t0 = u; t1 = w; t2 = y;
-  sort3(t0, t1, t2);
-  if (set128_has(hs3, key3(t0, t1, t2))) return;
-  t0 = u; t1 = x; t2 = y;
-  sort3(t0, t1, t2);
-  if (set128_has(hs3, key3(t0, t1, t2))) return;
-  t0 = w; t1 = x; t2 = y;
-  sort3(t0, t1, t2);
-  if (set128_has(hs3, key3(t0, t1, t2))) return;
+  if (has3(v.hs3, u, w, x) || has3(v.hs3, u, w, y) || has3(v.hs3, u, x, y) || has3(v.hs3, w, x, y)) return;
   uint32_t q[4] = {u, w, x, y};
   for (int i = 1; i < 4; ++i) {
     const uint32_t k = q[i];
@@ -159,127 +125,251 @@ __device__ inline void j2_candidate(uint32_t u, uint32_t w, uint32_t x, uint32_t
     while (j >= 0 && q[j] > k) { q[j + 1] = q[j]; --j; }
     q[j + 1] = k;
   }
-  if (set128_has(hs4, key4(q[0], q[1], q[2], q[3]))) return;
+  if (set128_has(v.hs4, key4(q[0], q[1], q[2], q[3]))) return;
   // local positions u=0, w=1, x=2, y=3
-  const uint32_t p = 1u | (pair_bit(hs2, bits, W, u, x) << 1) | (pair_bit(hs2, bits, W, w, x) << 2) |
-                     (pair_bit(hs2, bits, W, u, y) << 4) | (pair_bit(hs2, bits, W, w, y) << 5) |
-                     (pair_bit(hs2, bits, W, x, y) << 7);
+  const uint32_t p = 1u | (has2(v.hs2, u, x) << 1) | (has2(v.hs2, w, x) << 2) | (has2(v.hs2, u, y) << 4) |
+                     (has2(v.hs2, w, y) << 5) | (has2(v.hs2, x, y) << 7);
   const uint8_t cls = lut[p];
   if (cls != 0xFF) atomicAdd(&h[cls], 1ull);
 }
 
-__global__ void __launch_bounds__(kThreads) k_sample_j2_k4(
-    const uint32_t* __restrict__ idx, uint64_t S, const uint32_t* __restrict__ e2, uint64_t n2,
-    const uint32_t* __restrict__ g2_off, const uint32_t* __restrict__ g2_adj, Set64 hs2, Set128 hs3, Set128 hs4,
-    const uint32_t* __restrict__ bits, uint32_t W, const uint8_t* __restrict__ lut_g,
-    unsigned long long* __restrict__ hist, unsigned long long* __restrict__ ps) {
-  __shared__ uint8_t lut[2048];
-  __shared__ unsigned long long h_lds[256];
-  load_lut(lut, lut_g, 2048);
-  h_lds[threadIdx.x] = 0;
-  __syncthreads();
-  for (uint64_t s = blockIdx.x; s < S; s += gridDim.x) {
-    const uint64_t i = idx[s];
-    if (i >= n2) continue;
-    unsigned long long* h = ps ? ps + s * 256 : h_lds;
-    const uint32_t u = e2[2 * i], w = e2[2 * i + 1];
-    const uint32_t ub = g2_off[u], du = g2_off[u + 1] - ub;
-    const uint32_t wb = g2_off[w], dw = g2_off[w + 1] - wb;
+__device__ void sample_j2_k4_hash(const View& v, const Draws& d, uint32_t part, uint32_t n_parts,
+                                  const uint8_t* lut, unsigned long long* h_lds, unsigned long long* rows) {
+  for (uint64_t s = part; s < d.S[2]; s += n_parts) {
+    const uint64_t i = d.at(2, s);
+    if (i >= d.n[2]) continue;
+    unsigned long long* h = row_or(rows, s, h_lds);
+    const uint32_t u = v.e2[2 * i], w = v.e2[2 * i + 1];
+    const uint32_t ub = v.g2_off[u], du = v.g2_off[u + 1] - ub;
+    const uint32_t wb = v.g2_off[w], dw = v.g2_off[w + 1] - wb;
     const uint64_t nL = uint64_t(du) + dw;
-    auto valid = [&](uint32_t p, uint32_t x) {
-      return x != u && x != w && (p < du || !pair_bit(hs2, bits, W, u, x));
-    };
+    auto valid = [&](uint32_t p, uint32_t x) { return x != u && x != w && (p < du || !has2(v.hs2, u, x)); };
     // both other nodes adjacent to e
     const uint64_t npairs = nL * (nL - 1) / 2;
     for (uint64_t t = threadIdx.x; t < npairs; t += kThreads) {
       uint32_t p, q;
       pair_from_index(t, nL, p, q);
-      const uint32_t x = nodeL(g2_adj, ub, du, wb, p), y = nodeL(g2_adj, ub, du, wb, q);
+      const uint32_t x = nodeL(v.g2_adj, ub, du, wb, p), y = nodeL(v.g2_adj, ub, du, wb, q);
       if (!valid(p, x) || !valid(q, y)) continue;
-      j2_candidate(u, w, x, y, hs2, hs3, hs4, bits, W, lut, h);
+      j2_candidate(v, u, w, x, y, lut, h);
     }
     // x adjacent to e, y adjacent to x only
     for (uint32_t p = 0; p < nL; ++p) {
-      const uint32_t x = nodeL(g2_adj, ub, du, wb, p);
+      const uint32_t x = nodeL(v.g2_adj, ub, du, wb, p);
       if (!valid(p, x)) continue;
-      const uint32_t xb = g2_off[x], xe = g2_off[x + 1];
+      const uint32_t xb = v.g2_off[x], xe = v.g2_off[x + 1];
       for (uint32_t yi = xb + threadIdx.x; yi < xe; yi += kThreads) {
-        const uint32_t y = g2_adj[yi];
-        if (y == u || y == w || pair_bit(hs2, bits, W, u, y) || pair_bit(hs2, bits, W, w, y)) continue;
-        j2_candidate(u, w, x, y, hs2, hs3, hs4, bits, W, lut, h);
+        const uint32_t y = v.g2_adj[yi];
+        if (y == u || y == w || has2(v.hs2, u, y) || has2(v.hs2, w, y)) continue;
+        j2_candidate(v, u, w, x, y, lut, h);
       }
     }
   }
-  __syncthreads();
-  flush(h_lds, hist + kRaw, 256);
 }
 
-// order 3, j = 3: the sampled 3-node hyperedge with its pairs
-__global__ void __launch_bounds__(kThreads) k_sample_j3_k3(const uint32_t* __restrict__ idx, uint64_t S,
-                                                           const uint32_t* __restrict__ e3, uint64_t n3, Set64 hs2,
-                                                           const uint32_t* __restrict__ bits, uint32_t W,
-                                                           const uint8_t* __restrict__ lut_g,
-                                                           unsigned long long* __restrict__ hist,
-                                                           unsigned long long* __restrict__ ps) {
-  __shared__ uint8_t lut[16];
-  __shared__ unsigned long long h_lds[256];
-  load_lut(lut, lut_g, 16);
-  h_lds[threadIdx.x] = 0;
-  __syncthreads();
-  for (uint64_t s = uint64_t(blockIdx.x) * kThreads + threadIdx.x; s < S; s += uint64_t(gridDim.x) * kThreads) {
-    const uint64_t i = idx[s];
-    if (i >= n3) continue;
-    unsigned long long* h = ps ? ps + s * 256 : h_lds;
-    const uint32_t a = e3[3 * i], b = e3[3 * i + 1], c = e3[3 * i + 2];
-    const uint32_t p = (1u << 3) | pair_bit(hs2, bits, W, a, b) | (pair_bit(hs2, bits, W, a, c) << 1) |
-                       (pair_bit(hs2, bits, W, b, c) << 2);
-    atomicAdd(&h[lut[p]], 1ull);
+// j = 2 at order 4 with adjacency bit rows.  The kept sets for the sampled
+// pair e = {u, w} are e u {x, y} connected through pairs and holding no larger
+// hyperedge: none of {u,w,x}, {u,w,y}, {u,x,y}, {w,x,y} is a 3-node hyperedge
+// and {u,w,x,y} is not a 4-node hyperedge.  With T = {c : {u,w,c} is a 3-node
+// hyperedge} and X = T u e, the count by pairwise pattern is
+//   (pairs {x, y} outside X that connect e u {x, y} through pairs)
+//   - (those of them that close a 3-node hyperedge with u or with w, or a
+//      4-node hyperedge with e).
+// First term, with popcounts over bit rows: A = (N(u) u N(w)) \ X; every such
+// pair has x in A and either y in A with y > x, or y a neighbour of x outside
+// N(u) u N(w) u X.  Second term: the 3-node hyperedges at u and at w and the
+// 4-node hyperedges at u, each pair taken once.  One workgroup per sample.
+constexpr uint32_t kMaxWordsJ2 = kBitsetMaxNodes / 32;
+static_assert(kMaxWordsJ2 <= kThreads, "one thread per bit-row word");
+
+struct J2Lds {
+  uint32_t RU[kMaxWordsJ2], RW[kMaxWordsJ2], XS[kMaxWordsJ2], AS[kMaxWordsJ2];
+  uint32_t xs[kBitsetMaxNodes];
+  uint32_t wave_tot[kWavesPerBlock];
+  uint32_t red[21];
+};
+
+__device__ inline uint32_t wave_sum32(uint32_t x) {
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) x += __shfl_xor(x, o, kWave);
+  return x;
+}
+
+__device__ inline uint32_t node_bit(const uint32_t* row, uint32_t x) { return (row[x >> 5] >> (x & 31)) & 1u; }
+
+__device__ void sample_j2_k4_bits(const View& v, const Draws& d, uint32_t part, uint32_t n_parts, J2Lds& L,
+                                  const uint8_t* lut, unsigned long long* h_lds, unsigned long long* rows) {
+  const uint32_t tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
+  const uint32_t W = v.W;
+  const uint32_t* bits = v.bits;
+  for (uint64_t s = part; s < d.S[2]; s += n_parts) {
+    const uint64_t i = d.at(2, s);
+    if (i >= d.n[2]) continue;
+    unsigned long long* h = row_or(rows, s, h_lds);
+    const uint32_t u = v.e2[2 * i], w = v.e2[2 * i + 1];
+    if (tid < W) {
+      L.RU[tid] = bits[uint64_t(u) * W + tid];
+      L.RW[tid] = bits[uint64_t(w) * W + tid];
+      L.XS[tid] = 0;
+    }
+    if (tid < 21) L.red[tid] = 0;
+    __syncthreads();
+    if (tid == 0) {
+      atomicOr(&L.XS[u >> 5], 1u << (u & 31));
+      atomicOr(&L.XS[w >> 5], 1u << (w & 31));
+    }
+    const uint32_t u0 = v.i3_off[u], u1 = v.i3_off[u + 1];
+    for (uint32_t p = u0 + tid; p < u1; p += kThreads) {
+      const uint32_t* t = v.e3 + 3ull * v.i3_idx[p];
+      if (t[0] == w || t[1] == w || t[2] == w) {
+        const uint32_t c = t[0] ^ t[1] ^ t[2] ^ u ^ w;
+        atomicOr(&L.XS[c >> 5], 1u << (c & 31));
+      }
+    }
+    __syncthreads();
+    // A, compacted in ascending node order
+    uint32_t a = 0;
+    if (tid < W) {
+      a = (L.RU[tid] | L.RW[tid]) & ~L.XS[tid];
+      L.AS[tid] = a;
+    }
+    uint32_t wtot;
+    uint32_t off = wave_exclusive_scan(__popc(a), &wtot);
+    if (lane == 0) L.wave_tot[wv] = wtot;
+    __syncthreads();
+    uint32_t nA = 0;
+    for (uint32_t q = 0; q < uint32_t(kWavesPerBlock); ++q) {
+      if (q < wv) off += L.wave_tot[q];
+      nA += L.wave_tot[q];
+    }
+    while (a) {
+      L.xs[off++] = (tid << 5) | uint32_t(__ffs(a) - 1);
+      a &= a - 1;
+    }
+    __syncthreads();
+    // first term, by x's pattern to e (3) x y's pattern to u, w, x (7)
+    uint32_t acc[3][7];
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int j = 0; j < 7; ++j) acc[c][j] = 0;
+    const uint32_t n_tasks = nA * W;
+    for (uint32_t t = tid; t < n_tasks; t += kThreads) {
+      const uint32_t xi = t / W, wd = t - xi * W;
+      const uint32_t x = L.xs[xi];
+      const uint32_t xc = node_bit(L.RU, x) | (node_bit(L.RW, x) << 1);
+      const uint32_t rx = bits[uint64_t(x) * W + wd];
+      const uint32_t ru = L.RU[wd], rw = L.RW[wd];
+      const uint32_t yA = L.AS[wd] & mask_gt(x, wd);
+      const uint32_t m10 = yA & ru & ~rw, m01 = yA & ~ru & rw, m11 = yA & ru & rw;
+      uint32_t c7[7];
+      c7[0] = __popc(m10 & ~rx);
+      c7[1] = __popc(m10 & rx);
+      c7[2] = __popc(m01 & ~rx);
+      c7[3] = __popc(m01 & rx);
+      c7[4] = __popc(m11 & ~rx);
+      c7[5] = __popc(m11 & rx);
+      c7[6] = __popc(rx & ~(ru | rw | L.XS[wd]));
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int j = 0; j < 7; ++j) acc[c][j] += xc == uint32_t(c + 1) ? c7[j] : 0u;
+    }
+    // second term: each pair {x, y} outside X whose set holds a larger hyperedge
+    auto remove = [&](uint32_t x, uint32_t y) {
+      if (node_bit(L.XS, x) | node_bit(L.XS, y)) return;
+      const uint32_t pat = 1u | (node_bit(L.RU, x) << 1) | (node_bit(L.RW, x) << 2) | (node_bit(L.RU, y) << 4) |
+                           (node_bit(L.RW, y) << 5) | (bit_of(bits, W, x, y) << 7);
+      const uint8_t cls = lut[pat];
+      if (cls != 0xFF) atomicAdd(&h[cls], ~0ull);   // minus one
+    };
+    for (uint32_t p = u0 + tid; p < u1; p += kThreads) {
+      const uint32_t* t = v.e3 + 3ull * v.i3_idx[p];
+      if (t[0] == w || t[1] == w || t[2] == w) continue;
+      remove(t[0] == u ? t[1] : t[0], t[2] == u ? t[1] : t[2]);
+    }
+    const uint32_t w0 = v.i3_off[w], w1 = v.i3_off[w + 1];
+    for (uint32_t p = w0 + tid; p < w1; p += kThreads) {
+      const uint32_t* t = v.e3 + 3ull * v.i3_idx[p];
+      if (t[0] == u || t[1] == u || t[2] == u) continue;
+      const uint32_t x = t[0] == w ? t[1] : t[0], y = t[2] == w ? t[1] : t[2];
+      if (has3(v.hs3, u, x, y)) continue;   // taken at u
+      remove(x, y);
+    }
+    const uint32_t f0 = v.i4_off[u], f1 = v.i4_off[u + 1];
+    for (uint32_t p = f0 + tid; p < f1; p += kThreads) {
+      const uint32_t* f = v.e4 + 4ull * v.i4_idx[p];
+      const uint32_t f_0 = f[0], f_1 = f[1], f_2 = f[2], f_3 = f[3];
+      if (f_0 != w && f_1 != w && f_2 != w && f_3 != w) continue;
+      // the two members other than u and w, ascending
+      uint32_t x = 0xFFFFFFFFu, y = 0xFFFFFFFFu;
+      for (const uint32_t m : {f_0, f_1, f_2, f_3}) {
+        if (m == u || m == w) continue;
+        if (x == 0xFFFFFFFFu) x = m; else y = m;
+      }
+      if (has3(v.hs3, u, x, y) || has3(v.hs3, w, x, y)) continue;   // taken at u or w
+      remove(x, y);
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int j = 0; j < 7; ++j) {
+        const uint32_t sum = wave_sum32(acc[c][j]);
+        if (lane == 0 && sum) atomicAdd(&L.red[c * 7 + j], sum);
+      }
+    __syncthreads();
+    if (tid < 21 && L.red[tid]) {
+      // y's pattern (bit 0: to u, bit 1: to w, bit 2: to x) of each column
+      const uint32_t ycol = tid % 7;
+      const uint32_t yp = ycol == 6 ? 4u : ((ycol >> 1) + 1) | ((ycol & 1u) << 2);
+      const uint32_t xc = tid / 7 + 1;
+      const uint32_t pat = 1u | ((xc & 1u) << 1) | ((xc >> 1) << 2) | ((yp & 1u) << 4) | (((yp >> 1) & 1u) << 5) |
+                           ((yp >> 2) << 7);
+      atomicAdd(&h[lut[pat]], (unsigned long long)L.red[tid]);
+    }
+    __syncthreads();
   }
-  __syncthreads();
-  flush(h_lds, hist + kRaw, 256);
+}
+
+// order 3, j = 3: the sampled 3-node hyperedge with its pairs.  One thread per
+// sample.
+__device__ void sample_j3_k3(const View& v, const Draws& d, uint32_t part, uint32_t n_parts, const uint8_t* lut,
+                             unsigned long long* h_lds, unsigned long long* rows) {
+  for (uint64_t s = uint64_t(part) * kThreads + threadIdx.x; s < d.S[3]; s += uint64_t(n_parts) * kThreads) {
+    const uint64_t i = d.at(3, s);
+    if (i >= d.n[3]) continue;
+    const uint32_t a = v.e3[3 * i], b = v.e3[3 * i + 1], c = v.e3[3 * i + 2];
+    const uint32_t p = (1u << 3) | pair_bit(v.hs2, v.bits, v.W, a, b) | (pair_bit(v.hs2, v.bits, v.W, a, c) << 1) |
+                       (pair_bit(v.hs2, v.bits, v.W, b, c) << 2);
+    atomicAdd(&row_or(rows, s, h_lds)[lut[p]], 1ull);
+  }
 }
 
 // order 3, j = 2: the sampled pair {u, w} and one neighbour x of u or w
 // (taken once) such that {u, w, x} is not a 3-node hyperedge.  One wavefront
 // per sample.
-__global__ void __launch_bounds__(kThreads) k_sample_j2_k3(const uint32_t* __restrict__ idx, uint64_t S,
-                                                           const uint32_t* __restrict__ e2, uint64_t n2,
-                                                           const uint32_t* __restrict__ g2_off,
-                                                           const uint32_t* __restrict__ g2_adj, Set64 hs2,
-                                                           Set128 hs3, const uint32_t* __restrict__ bits, uint32_t W,
-                                                           const uint8_t* __restrict__ lut_g,
-                                                           unsigned long long* __restrict__ hist,
-                                                           unsigned long long* __restrict__ ps) {
-  __shared__ uint8_t lut[16];
-  __shared__ unsigned long long h_lds[256];
-  load_lut(lut, lut_g, 16);
-  h_lds[threadIdx.x] = 0;
-  __syncthreads();
+__device__ void sample_j2_k3(const View& v, const Draws& d, uint32_t part, uint32_t n_parts, const uint8_t* lut,
+                             unsigned long long* h_lds, unsigned long long* rows) {
   const int lane = threadIdx.x & (kWave - 1);
-  const uint64_t wave = uint64_t(blockIdx.x) * kWavesPerBlock + threadIdx.x / kWave;
-  const uint64_t n_waves = uint64_t(gridDim.x) * kWavesPerBlock;
-  for (uint64_t s = wave; s < S; s += n_waves) {
-    const uint64_t i = idx[s];
-    if (i >= n2) continue;
-    const uint32_t u = e2[2 * i], w = e2[2 * i + 1];
-    const uint32_t ub = g2_off[u], du = g2_off[u + 1] - ub;
-    const uint32_t wb = g2_off[w], dw = g2_off[w + 1] - wb;
-    unsigned long long* h = ps ? ps + s * 256 : h_lds;
+  const int wv = threadIdx.x / kWave;
+  for (uint64_t s = uint64_t(part) * kWavesPerBlock + wv; s < d.S[2]; s += uint64_t(n_parts) * kWavesPerBlock) {
+    const uint64_t i = d.at(2, s);
+    if (i >= d.n[2]) continue;
+    const uint32_t u = v.e2[2 * i], w = v.e2[2 * i + 1];
+    const uint32_t ub = v.g2_off[u], du = v.g2_off[u + 1] - ub;
+    const uint32_t wb = v.g2_off[w], dw = v.g2_off[w + 1] - wb;
+    unsigned long long* h = row_or(rows, s, h_lds);
     for (uint32_t p = lane; p < du + dw; p += kWave) {
-      const uint32_t x = nodeL(g2_adj, ub, du, wb, p);
+      const uint32_t x = nodeL(v.g2_adj, ub, du, wb, p);
       if (x == u || x == w) continue;
-      const uint32_t ux = pair_bit(hs2, bits, W, u, x);
+      const uint32_t ux = pair_bit(v.hs2, v.bits, v.W, u, x);
       if (p >= du && ux) continue;            // taken from u's row
-      uint32_t t0 = u, t1 = w, t2 = x;
-      sort3(t0, t1, t2);
-      if (set128_has(hs3, key3(t0, t1, t2))) continue;
-      const uint32_t wx = pair_bit(hs2, bits, W, w, x);
+      if (has3(v.hs3, u, w, x)) continue;
+      const uint32_t wx = pair_bit(v.hs2, v.bits, v.W, w, x);
       // local positions u=0, w=1, x=2
       atomicAdd(&h[lut[1u | (ux << 1) | (wx << 2)]], 1ull);
     }
   }
-  __syncthreads();
-  flush(h_lds, hist + kRaw, 256);
 }
 
 struct ScaleArgs {
@@ -289,18 +379,90 @@ struct ScaleArgs {
   uint8_t countmax[256];
 };
 
-// est_m = raw_m * |E_mc| / (S_mc * countmax_m) in fp64, rounded once to fp32;
-// 0 when the stratum was not sampled
-__global__ void k_scale(const unsigned long long* __restrict__ hist, int n_classes, ScaleArgs args,
-                        float* __restrict__ est, int64_t* __restrict__ raw) {
+struct SampledArgs {
+  View v;
+  Draws d;
+  const uint8_t* lut;
+  uint32_t blocks[5];            // workgroups of strata 2, 3, 4 (in this order in the grid)
+  unsigned long long* rows[5];   // per-sample rows (256 counters) of each stratum, or null
+  unsigned long long* hist;      // 256 raw counters, zero on entry; left zero after scaling
+  unsigned int* ticket;          // workgroups done; zero on entry and left zero
+  float* est;                    // null: no scaling (row mode)
+  int64_t* raw;
+  int n_classes;
+};
+
+template <int K, bool BITS>
+struct SampledLds {
+  uint32_t unused;
+};
+template <>
+struct SampledLds<4, true> {
+  union {
+    B4Scratch b4[kWavesPerBlock];
+    J2Lds j2;
+  };
+};
+template <>
+struct SampledLds<4, false> {
+  uint32_t unused;
+};
+
+// Every stratum's samples in one launch.  The grid holds a.blocks[2]
+// workgroups for the sampled pairs, then a.blocks[3] for the 3-node and
+// a.blocks[4] for the 4-node hyperedges.  Each workgroup adds its LDS counts to
+// a.hist; the last one to finish scales them (Algorithm 4's correction:
+// est_m = raw_m * |E_mc| / (S_mc * countmax_m) in fp64, rounded once to fp32,
+// 0 when the stratum was not sampled) and clears a.hist and a.ticket.
+template <int K, bool BITS>
+__global__ void __launch_bounds__(kThreads) k_sampled(SampledArgs a, ScaleArgs sc) {
+  constexpr int kLut = K == 4 ? 2048 : 16;
+  __shared__ uint8_t lut[kLut];
+  __shared__ unsigned long long h_lds[256];
+  __shared__ SampledLds<K, BITS> lds;
+  __shared__ uint32_t last;
+  load_lut(lut, a.lut, kLut);
+  h_lds[threadIdx.x] = 0;
+  __syncthreads();
+  uint32_t b = blockIdx.x;
+  if (b < a.blocks[2]) {
+    if constexpr (K == 4 && BITS)
+      sample_j2_k4_bits(a.v, a.d, b, a.blocks[2], lds.j2, lut, h_lds, a.rows[2]);
+    else if constexpr (K == 4)
+      sample_j2_k4_hash(a.v, a.d, b, a.blocks[2], lut, h_lds, a.rows[2]);
+    else
+      sample_j2_k3(a.v, a.d, b, a.blocks[2], lut, h_lds, a.rows[2]);
+  } else if ((b -= a.blocks[2]) < a.blocks[3]) {
+    if constexpr (K == 4 && BITS)
+      sample_j3_k4<true>(a.v, a.d, b, a.blocks[3], lds.b4, lut, h_lds, a.rows[3]);
+    else if constexpr (K == 4)
+      sample_j3_k4<false>(a.v, a.d, b, a.blocks[3], nullptr, lut, h_lds, a.rows[3]);
+    else
+      sample_j3_k3(a.v, a.d, b, a.blocks[3], lut, h_lds, a.rows[3]);
+  } else if (K == 4) {
+    b -= a.blocks[3];
+    sample_j4(a.v, a.d, b, a.blocks[4], lut, h_lds, a.rows[4]);
+  }
+  __syncthreads();
+  flush(h_lds, a.hist, 256);
+  if (!a.est) return;
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) last = atomicAdd(a.ticket, 1u) == gridDim.x - 1;
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
   const int c = threadIdx.x;
-  if (c >= n_classes) return;
-  const unsigned long long r = hist[kRaw + c];
-  const int j = args.maxcard[c];
-  double e = 0.0;
-  if (args.s_by_size[j] > 0.0) e = (double(r) * args.n_by_size[j]) / (args.s_by_size[j] * double(args.countmax[c]));
-  est[c] = float(e);
-  if (raw) raw[c] = int64_t(r);
+  const unsigned long long r = __hip_atomic_load(a.hist + c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (c < a.n_classes) {
+    const int j = sc.maxcard[c];
+    double e = 0.0;
+    if (sc.s_by_size[j] > 0.0) e = (double(r) * sc.n_by_size[j]) / (sc.s_by_size[j] * double(sc.countmax[c]));
+    a.est[c] = float(e);
+    if (a.raw) a.raw[c] = int64_t(r);
+  }
+  a.hist[c] = 0;
+  if (c == 0) *a.ticket = 0;
 }
 
 unsigned grid_for(uint64_t items, uint64_t per_block, unsigned cap = 512) {
@@ -310,18 +472,72 @@ unsigned grid_for(uint64_t items, uint64_t per_block, unsigned cap = 512) {
   return unsigned(g);
 }
 
-int ensure_index_capacity(hm_graph* H, uint64_t n) {
-  if (n <= H->sample_cap) return HM_OK;
-  if (H->sample_idx) {
-    HM_HIP(hipDeviceSynchronize());
-    dfree(H->sample_idx);
-    H->sample_idx = nullptr;
-    H->sample_cap = 0;
+uint32_t blocks_for(uint64_t items, uint64_t per_block, uint32_t cap) {
+  if (!items) return 0;
+  return uint32_t(std::min<uint64_t>((items + per_block - 1) / per_block, cap));
+}
+
+// Launch the sampler over every stratum: explicit indices (idx[j] non-null)
+// or draws of the stratum's stream under `seed`.  rows != null: sample s of
+// stratum j adds to row rows[row0[j] + s] and nothing is scaled; otherwise
+// est (and raw) receive the scaled (and raw) counts.
+int launch_sampled(const hm_graph* H, int k, const uint32_t* const idx[5], const uint64_t S[5], uint64_t seed,
+                   unsigned long long* rows, const uint64_t row0[5], float* est, int64_t* raw, hipStream_t st) {
+  const uint8_t *lut4 = nullptr, *lut3 = nullptr;
+  HM_TRY(device_luts(H->device, &lut4, &lut3));
+  const bool bits = H->bits != nullptr;
+  if (k == 4 && bits && H->words > kMaxWordsJ2) {
+    set_error("bit rows of %u words exceed the sampler's %u", H->words, kMaxWordsJ2);
+    return HM_EINTERNAL;
   }
-  void* p = nullptr;
-  HM_TRY(dalloc(&p, n * sizeof(uint32_t)));
-  H->sample_idx = static_cast<uint32_t*>(p);
-  H->sample_cap = n;
+  SampledArgs a;
+  a.v = view_of(H);
+  for (int j = 0; j < 5; ++j) {
+    const bool in = j >= 2 && j <= k;
+    a.d.idx[j] = in ? idx[j] : nullptr;
+    a.d.S[j] = in ? S[j] : 0;
+    a.d.n[j] = in ? H->n_by_size[j] : 0;
+    a.rows[j] = (rows && in) ? rows + row0[j] * 256 : nullptr;
+    a.blocks[j] = 0;
+  }
+  a.d.seed = seed;
+  a.lut = k == 4 ? lut4 : lut3;
+  if (k == 4) {
+    a.blocks[2] = blocks_for(a.d.S[2], 1, 2048);
+    a.blocks[3] = blocks_for(a.d.S[3], kWavesPerBlock, 1024);
+    a.blocks[4] = blocks_for(a.d.S[4], kThreads, 256);
+  } else {
+    a.blocks[2] = blocks_for(a.d.S[2], kWavesPerBlock, 1024);
+    a.blocks[3] = blocks_for(a.d.S[3], kThreads, 256);
+  }
+  uint32_t grid = a.blocks[2] + a.blocks[3] + a.blocks[4];
+  if (grid == 0) {   // nothing sampled: one workgroup still scales (to zeros)
+    a.blocks[2] = 1;
+    grid = 1;
+  }
+  a.hist = H->sample_hist;
+  a.ticket = reinterpret_cast<unsigned int*>(H->sample_hist + 256);
+  a.est = rows ? nullptr : est;
+  a.raw = rows ? nullptr : raw;
+  const ClassTables& t = class_tables();
+  a.n_classes = t.n_classes[k];
+  ScaleArgs sc;
+  for (int j = 0; j < 5; ++j) {
+    sc.n_by_size[j] = (j >= 2 && j <= 4) ? double(H->n_by_size[j]) : 0.0;
+    sc.s_by_size[j] = (j >= 2 && j <= k) ? double(S[j]) : 0.0;
+  }
+  for (int c = 0; c < 256; ++c) {
+    sc.maxcard[c] = c < t.n_classes[k] ? t.maxcard[k][c] : 0;
+    sc.countmax[c] = c < t.n_classes[k] ? t.countmax[k][c] : 1;
+  }
+  ProfileScope pscope("k_sampled", st);
+  if (k == 4 && bits)
+    k_sampled<4, true><<<grid, kThreads, 0, st>>>(a, sc);
+  else if (k == 4)
+    k_sampled<4, false><<<grid, kThreads, 0, st>>>(a, sc);
+  else
+    k_sampled<3, false><<<grid, kThreads, 0, st>>>(a, sc);
+  HM_HIP(hipGetLastError());
   return HM_OK;
 }
 
@@ -356,95 +572,22 @@ int sample_sizes(const hm_graph* H, int k, double fraction, int allocation, uint
   return HM_OK;
 }
 
-// Enumerate around explicit samples (device index arrays).  With ps == null
-// the raw counts go to hm_graph::hist; otherwise sample s of stratum j adds
-// to row ps[row0[j] + s] (256 counters per row, zeroed by the caller).
+// Enumerate around explicit samples (device index arrays): sample s of stratum
+// j adds to row ps[row0[j] + s] (256 counters per row, zeroed by the caller).
 int enumerate_samples(const hm_graph* H, int k, const uint32_t* const idx[5], const uint64_t S[5],
                       unsigned long long* ps, const uint64_t row0[5], hipStream_t st) {
-  const uint8_t *lut4 = nullptr, *lut3 = nullptr;
-  HM_TRY(device_luts(H->device, &lut4, &lut3));
-  const uint64_t n2 = H->n_by_size[2], n3 = H->n_by_size[3], n4 = H->n_by_size[4];
-  auto rows = [&](int j) { return ps ? ps + row0[j] * 256 : nullptr; };
-  if (k == 4) {
-    if (S[4]) {
-      ProfileScope pscope("k_sample_j4", st);
-      k_sample_j4<<<grid_for(S[4], kThreads), kThreads, 0, st>>>(idx[4], S[4], H->e4, n4, H->hs2, H->hs3, H->bits,
-                                                                  H->words, lut4, H->hist, rows(4));
-    }
-    if (S[3]) {
-      if (H->bits) {
-        ProfileScope pscope("k_sample_j3_bits", st);
-        k_sample_j3_bits<<<grid_for(S[3], kWavesPerBlock), kThreads, 0, st>>>(
-            idx[3], S[3], H->e3, n3, H->e4, H->i3_off, H->i3_idx, H->i4_off, H->i4_idx, H->bits, H->words, lut4,
-            H->hist, rows(3));
-      } else {
-        ProfileScope pscope("k_sample_j3_hash", st);
-        k_sample_j3_hash<<<grid_for(S[3], kWavesPerBlock), kThreads, 0, st>>>(
-            idx[3], S[3], H->e3, n3, H->g2_off, H->g2_adj, H->i3_off, H->i3_idx, H->hs2, H->hs3, H->hs4, lut4,
-            H->hist, rows(3));
-      }
-    }
-    if (S[2]) {
-      ProfileScope pscope("k_sample_j2_k4", st);
-      k_sample_j2_k4<<<grid_for(S[2], 1, 1024), kThreads, 0, st>>>(idx[2], S[2], H->e2, n2, H->g2_off, H->g2_adj,
-                                                                    H->hs2, H->hs3, H->hs4, H->bits, H->words, lut4,
-                                                                    H->hist, rows(2));
-    }
-  } else {
-    if (S[3]) {
-      ProfileScope pscope("k_sample_j3_k3", st);
-      k_sample_j3_k3<<<grid_for(S[3], kThreads), kThreads, 0, st>>>(idx[3], S[3], H->e3, n3, H->hs2, H->bits,
-                                                                     H->words, lut3, H->hist, rows(3));
-    }
-    if (S[2]) {
-      ProfileScope pscope("k_sample_j2_k3", st);
-      k_sample_j2_k3<<<grid_for(S[2], kWavesPerBlock), kThreads, 0, st>>>(idx[2], S[2], H->e2, n2, H->g2_off,
-                                                                          H->g2_adj, H->hs2, H->hs3, H->bits,
-                                                                          H->words, lut3, H->hist, rows(2));
-    }
+  if (!ps) {
+    set_error("enumerate_samples needs per-sample rows");
+    return HM_EINTERNAL;
   }
-  HM_HIP(hipGetLastError());
-  return HM_OK;
+  return launch_sampled(H, k, idx, S, 0, ps, row0, nullptr, nullptr, st);
 }
 
 // Enumerate around explicit samples and scale (Algorithm 4).
 int sampled_from_indices(const hm_graph* H, int k, const uint32_t* const idx[5], const uint64_t S[5], float* est,
                          int64_t* raw, hipStream_t st) {
-  HM_TRY(fill_u64(H->hist, 0, 4 * 256, st));
   const uint64_t row0[5] = {0, 0, 0, 0, 0};
-  HM_TRY(enumerate_samples(H, k, idx, S, nullptr, row0, st));
-  const ClassTables& t = class_tables();
-  ScaleArgs a;
-  for (int j = 0; j < 5; ++j) {
-    a.n_by_size[j] = (j >= 2 && j <= 4) ? double(H->n_by_size[j]) : 0.0;
-    a.s_by_size[j] = (j >= 2 && j <= k) ? double(S[j]) : 0.0;
-  }
-  for (int c = 0; c < 256; ++c) {
-    a.maxcard[c] = c < t.n_classes[k] ? t.maxcard[k][c] : 0;
-    a.countmax[c] = c < t.n_classes[k] ? t.countmax[k][c] : 1;
-  }
-  k_scale<<<1, 256, 0, st>>>(H->hist, t.n_classes[k], a, est, raw);
-  HM_HIP(hipGetLastError());
-  return HM_OK;
-}
-
-int draw_samples(hm_graph* H, int k, double fraction, uint64_t seed, int allocation, uint64_t S[5],
-                 const uint32_t* idx[5], hipStream_t st) {
-  HM_TRY(sample_sizes(H, k, fraction, allocation, S));
-  const uint64_t total = S[2] + S[3] + S[4];
-  HM_TRY(ensure_index_capacity(H, total + 1));
-  uint64_t off = 0;
-  for (int j = 0; j < 5; ++j) idx[j] = nullptr;
-  for (int j = 2; j <= k; ++j) {
-    idx[j] = H->sample_idx + off;
-    if (S[j]) {
-      k_draw<<<grid_for(S[j], 256, 1024), 256, 0, st>>>(H->sample_idx + off, S[j], H->n_by_size[j], seed,
-                                                         uint32_t(j));
-      HM_HIP(hipGetLastError());
-    }
-    off += S[j];
-  }
-  return HM_OK;
+  return launch_sampled(H, k, idx, S, 0, nullptr, row0, est, raw, st);
 }
 
 }  // namespace hm
@@ -494,9 +637,10 @@ int count_sampled(const hm_graph* H, int k, double fraction, uint64_t seed, int 
   }
   hipStream_t st = static_cast<hipStream_t>(stream);
   uint64_t S[5];
-  const uint32_t* idx[5];
-  HM_TRY(hm::draw_samples(const_cast<hm_graph*>(H), k, fraction, seed, allocation, S, idx, st));
-  return hm::sampled_from_indices(H, k, idx, S, est, raw, st);
+  HM_TRY(hm::sample_sizes(H, k, fraction, allocation, S));
+  const uint32_t* idx[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};   // drawn in the kernel
+  const uint64_t row0[5] = {0, 0, 0, 0, 0};
+  return hm::launch_sampled(H, k, idx, S, seed, nullptr, row0, est, raw, st);
 }
 
 int count_sampled_indices(const hm_graph* H, int k, const uint32_t* idx2, uint64_t s2, const uint32_t* idx3,
