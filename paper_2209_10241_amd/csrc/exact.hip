@@ -74,20 +74,6 @@ __global__ void __launch_bounds__(kThreads) k_case_c4_bits(View v, uint64_t n2, 
   flush(h_g2, hist + kG2, 256);
 }
 
-__global__ void __launch_bounds__(kThreads) k_case_c4_hash(View v, uint64_t n2, const uint8_t* __restrict__ lut_g,
-                                                           unsigned long long* __restrict__ hist) {
-  __shared__ uint8_t lut[2048];
-  __shared__ unsigned long long h_g2[256];
-  load_lut(lut, lut_g, 2048);
-  h_g2[threadIdx.x] = 0;
-  __syncthreads();
-  const uint64_t wave = uint64_t(blockIdx.x) * kWavesPerBlock + threadIdx.x / kWave;
-  const uint64_t n_waves = uint64_t(gridDim.x) * kWavesPerBlock;
-  for (uint64_t i = wave; i < n2; i += n_waves) c4_hash_item(v, v.e2[2 * i], v.e2[2 * i + 1], lut, h_g2);
-  __syncthreads();
-  flush(h_g2, hist + kG2, 256);
-}
-
 // (a) at order 3: one thread per 3-node hyperedge.
 __global__ void __launch_bounds__(kThreads) k_case_a3(View v, uint64_t n3, const uint8_t* __restrict__ lut_g,
                                                       unsigned long long* __restrict__ hist) {
@@ -118,21 +104,6 @@ __global__ void __launch_bounds__(kThreads) k_case_c3_bits(View v, uint64_t n2, 
     const uint64_t i = t / v.W;
     c3_bits_word(v, v.e2[2 * i], v.e2[2 * i + 1], uint32_t(t % v.W), acc);
   }
-  c3_flush(acc, lut, h_g2);
-  __syncthreads();
-  flush(h_g2, hist + kG2, 256);
-}
-
-__global__ void __launch_bounds__(kThreads) k_case_c3_hash(View v, uint64_t n2, const uint8_t* __restrict__ lut_g,
-                                                           unsigned long long* __restrict__ hist) {
-  __shared__ uint8_t lut[16];
-  __shared__ unsigned long long h_g2[256];
-  load_lut(lut, lut_g, 16);
-  h_g2[threadIdx.x] = 0;
-  __syncthreads();
-  C3Acc acc{0, 0, 0};
-  for (uint64_t i = uint64_t(blockIdx.x) * kThreads + threadIdx.x; i < n2; i += uint64_t(gridDim.x) * kThreads)
-    c3_hash_item(v, v.e2[2 * i], v.e2[2 * i + 1], acc);
   c3_flush(acc, lut, h_g2);
   __syncthreads();
   flush(h_g2, hist + kG2, 256);
@@ -187,17 +158,14 @@ int count_exact_impl(const hm_graph* H, int k, int64_t* counts, hipStream_t st) 
       ProfileScope ps("k_case_a4", st);
       k_case_a4<<<grid_threads(n4), kThreads, 0, st>>>(v, n4, lut4, H->hist);
     }
-    if (n3) {
-      ProfileScope ps(v.bits ? "k_case_b4_bits" : "k_case_b4", st);
-      k_case_b4<<<grid_waves(n3), kThreads, 0, st>>>(v, n3, lut4, H->hist);
-    }
-    if (n2) {
-      if (v.bits) {
+    if (v.bits) {
+      if (n3) {
+        ProfileScope ps("k_case_b4_bits", st);
+        k_case_b4<<<grid_waves(n3), kThreads, 0, st>>>(v, n3, lut4, H->hist);
+      }
+      if (n2) {
         ProfileScope ps("k_case_c4_bits", st);
         k_case_c4_bits<<<grid_waves(n2), kThreads, 0, st>>>(v, n2, lut4, H->hist);
-      } else {
-        ProfileScope ps("k_case_c4_hash", st);
-        k_case_c4_hash<<<grid_waves(n2), kThreads, 0, st>>>(v, n2, lut4, H->hist);
       }
     }
   } else {
@@ -205,16 +173,13 @@ int count_exact_impl(const hm_graph* H, int k, int64_t* counts, hipStream_t st) 
       ProfileScope ps("k_case_a3", st);
       k_case_a3<<<grid_threads(n3), kThreads, 0, st>>>(v, n3, lut3, H->hist);
     }
-    if (n2) {
-      if (v.bits) {
-        ProfileScope ps("k_case_c3_bits", st);
-        k_case_c3_bits<<<grid_threads(n2 * v.W), kThreads, 0, st>>>(v, n2, lut3, H->hist);
-      } else {
-        ProfileScope ps("k_case_c3_hash", st);
-        k_case_c3_hash<<<grid_threads(n2), kThreads, 0, st>>>(v, n2, lut3, H->hist);
-      }
+    if (v.bits && n2) {
+      ProfileScope ps("k_case_c3_bits", st);
+      k_case_c3_bits<<<grid_threads(n2 * v.W), kThreads, 0, st>>>(v, n2, lut3, H->hist);
     }
   }
+  HM_HIP(hipGetLastError());
+  if (!v.bits) HM_TRY(count_sparse(H, k, st));
   HM_HIP(hipGetLastError());
   k_combine<<<1, 256, 0, st>>>(H->hist, t.n_classes[k], pairs_only, counts);
   HM_HIP(hipGetLastError());

@@ -536,6 +536,8 @@ void release(hm_graph* H) {
   dfree(H->bits);
   dfree(H->hist);
   dfree(H->sample_hist);
+  dfree(H->pl_keys);
+  dfree(H->pl_edge);
   if (H->null_plan) destroy_null_plan(H->null_plan);
   H->null_plan = nullptr;
   if (H->proposal) destroy_proposal_cache(H->proposal);

@@ -148,6 +148,8 @@ uint64_t radix_ws_words(uint64_t n);
 int radix_sort_ws(unsigned long long* keys, uint32_t* vals, unsigned long long* keys_tmp, uint32_t* vals_tmp,
                   uint64_t n, int bits, uint32_t* ws, hipStream_t stream);
 int fill_u64(unsigned long long* p, unsigned long long value, uint64_t n, hipStream_t stream);
+// *out = max(*out, v[0..n)) (out zeroed by the caller)
+int max_u32(const uint32_t* v, uint64_t n, uint32_t* out, hipStream_t stream);
 
 // ----------------------------------------------------------------- profiling
 // While hm_profile_enable(1) is in effect, a scope records HIP events around
@@ -174,6 +176,11 @@ class ProfileScope {
 // ----------------------------------------------------------------- device allocations
 int dalloc(void** p, size_t bytes);
 void dfree(void* p);
+
+// Order-k counts of the pairs-only shapes and of case (b) without bit rows
+// into H->hist (case (a) is counted by the caller).
+int count_sparse(const hm_graph* H, int k, hipStream_t st);
+int ensure_pair_links(hm_graph* H, hipStream_t st);
 
 struct NullPlan;
 void destroy_null_plan(NullPlan* p);
@@ -221,6 +228,10 @@ struct hm_graph {
 
   // histogram scratch, reused by the counting calls (serialised per graph)
   unsigned long long* hist = nullptr;      // 4 x 256 counters
+  // pairs inside 3-node hyperedges, sorted ((x << 32) | y), with the position
+  // of their hyperedge in e3; built on first use without bit rows
+  unsigned long long* pl_keys = nullptr;
+  uint32_t* pl_edge = nullptr;
   // raw counters (256) and finished-workgroup ticket of the sampled counting
   // calls; zero between calls
   unsigned long long* sample_hist = nullptr;

@@ -1,0 +1,224 @@
+// Neighbourhood of one 3-node hyperedge without adjacency bit rows, counted
+// rather than enumerated (Algorithm 3's exploration around a 3-node
+// hyperedge; Algorithm 4's around a sampled one).
+//
+// For e = {a<b<c} the candidate sets are e u {v}.  A node v is *exceptional*
+// when {a,b,v}, {a,c,v} or {b,c,v} is another 3-node hyperedge or {a,b,c,v}
+// is a 4-node hyperedge; every other v has e as the only hyperedge of size
+// >= 3 in e u {v}, so its class depends only on which of a, b, c it is
+// paired with (the combination (av, bv, cv)).  The number of such v per
+// combination follows from |N(a)|, |N(b)|, |N(c)|, the three pairwise and the
+// triple intersection sizes (inclusion-exclusion, members of e excluded), less
+// the exceptional v of that combination; exceptional v are classified one by
+// one by fill-in.
+//
+// OWN = true (exact counting): a set is counted only when e is its
+// lexicographically smallest 3-node hyperedge and it is not a 4-node
+// hyperedge (those are counted on their own); the pairwise shape of counted
+// sets whose pairs connect them goes to h_sub.
+// OWN = false (sampling): every set whose largest hyperedge has 3 nodes
+// counts.
+//
+// One wavefront per hyperedge; per-class counters are LDS (or per-sample rows).
+#pragma once
+
+#include "hm_items.h"
+
+namespace hm {
+
+// Pairs inside 3-node hyperedges, sorted: keys (x << 32) | y with x < y, and
+// the position in e3 of the hyperedge each came from.
+struct PairLinks {
+  const unsigned long long* keys;
+  const uint32_t* edge;
+  uint64_t n;
+};
+
+__device__ inline uint64_t pl_lower(const PairLinks& pl, unsigned long long key) {
+  uint64_t lo = 0, hi = pl.n;
+  while (lo < hi) {
+    const uint64_t m = lo + ((hi - lo) >> 1);
+    if (pl.keys[m] < key) lo = m + 1; else hi = m;
+  }
+  return lo;
+}
+
+__device__ inline uint32_t deg2_of(const View& v, uint32_t x) { return v.g2_off[x + 1] - v.g2_off[x]; }
+
+__device__ inline uint32_t wave_sum_u32(uint32_t x) {
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) x += __shfl_xor(x, o, kWave);
+  return x;
+}
+
+// |N(s) n N(x)| and, with y given, |N(s) n N(x) n N(y)|, over s's row (wave)
+__device__ inline void row_probe(const View& v, uint32_t s, uint32_t x, uint32_t y, uint32_t& cx, uint32_t& cy,
+                                 uint32_t& cxy) {
+  const int lane = threadIdx.x & (kWave - 1);
+  uint32_t nx = 0, ny = 0, nxy = 0;
+  for (uint32_t p = v.g2_off[s] + lane; p < v.g2_off[s + 1]; p += kWave) {
+    const uint32_t z = v.g2_adj[p];
+    const uint32_t hx = has2(v.hs2, x, z), hy = has2(v.hs2, y, z);
+    nx += hx;
+    ny += hy;
+    nxy += hx & hy;
+  }
+  cx = wave_sum_u32(nx);
+  cy = wave_sum_u32(ny);
+  cxy = wave_sum_u32(nxy);
+}
+
+__device__ inline uint32_t row_count(const View& v, uint32_t s, uint32_t x) {
+  const int lane = threadIdx.x & (kWave - 1);
+  uint32_t n = 0;
+  for (uint32_t p = v.g2_off[s] + lane; p < v.g2_off[s + 1]; p += kWave) n += has2(v.hs2, x, v.g2_adj[p]);
+  return wave_sum_u32(n);
+}
+
+template <bool OWN>
+__device__ void b4_sparse(const View& v, const PairLinks& pl, uint32_t a, uint32_t b, uint32_t c, const uint8_t* lut,
+                          unsigned long long* h_main, unsigned long long* h_sub) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const uint32_t pab = has2(v.hs2, a, b), pac = has2(v.hs2, a, c), pbc = has2(v.hs2, b, c);
+  const uint32_t base_p = pab | (pac << 1) | (pbc << 2) | (1u << 3);
+  const uint32_t da = deg2_of(v, a), db = deg2_of(v, b), dc = deg2_of(v, c);
+  // intersections: the smallest row against the other two, then the smaller
+  // of the remaining two rows against the last
+  uint32_t cab, cac, cbc, tri;
+  if (da <= db && da <= dc) {
+    row_probe(v, a, b, c, cab, cac, tri);
+    cbc = db <= dc ? row_count(v, b, c) : row_count(v, c, b);
+  } else if (db <= dc) {
+    row_probe(v, b, a, c, cab, cbc, tri);
+    cac = da <= dc ? row_count(v, a, c) : row_count(v, c, a);
+  } else {
+    row_probe(v, c, a, b, cac, cbc, tri);
+    cab = da <= db ? row_count(v, a, b) : row_count(v, b, a);
+  }
+  // exceptional nodes, each once, by the first hyperedge that makes it one
+  // (slot 0..2: {a,b,v}, {a,c,v}, {b,c,v}; slot 3: {a,b,c,v}); per lane,
+  // the number of them in each pairwise combination
+  uint32_t dn1 = 0, dn2 = 0, dn3 = 0, dn4 = 0, dn5 = 0, dn6 = 0, dn7 = 0;
+  for (int slot = 0; slot < 4; ++slot) {
+    uint64_t lo = 0, hi = 0;
+    uint32_t q0 = 0, q1 = 0;   // the pair of this slot
+    if (slot < 3) {
+      q0 = slot < 2 ? a : b;
+      q1 = slot == 0 ? b : c;
+      const unsigned long long key = ((unsigned long long)q0 << 32) | q1;
+      lo = pl_lower(pl, key);
+      hi = pl_lower(pl, key + 1);
+    } else {
+      // 4-node hyperedges holding e, from the member with the fewest of them
+      const uint32_t fa = v.i4_off[a + 1] - v.i4_off[a], fb = v.i4_off[b + 1] - v.i4_off[b],
+                     fc = v.i4_off[c + 1] - v.i4_off[c];
+      const uint32_t s = (fa <= fb && fa <= fc) ? a : (fb <= fc ? b : c);
+      lo = v.i4_off[s];
+      hi = v.i4_off[s + 1];
+    }
+    for (uint64_t p = lo + lane; p < hi; p += kWave) {
+      uint32_t x;
+      uint32_t abv = 0, acv = 0, bcv = 0, quad = 0;
+      if (slot < 3) {
+        const uint32_t* f = v.e3 + 3ull * pl.edge[p];
+        x = f[0] ^ f[1] ^ f[2] ^ q0 ^ q1;
+        if (x == a || x == b || x == c) continue;   // e itself
+        if (slot == 0) {
+          abv = 1;
+        } else if (slot == 1) {
+          if (has3(v.hs3, a, b, x)) continue;
+          acv = 1;
+        } else {
+          if (has3(v.hs3, a, b, x) || has3(v.hs3, a, c, x)) continue;
+          bcv = 1;
+        }
+      } else {
+        const uint32_t* f = v.e4 + 4ull * v.i4_idx[p];
+        const uint32_t f0 = f[0], f1 = f[1], f2 = f[2], f3 = f[3];
+        const uint32_t hit = uint32_t(f0 == a || f0 == b || f0 == c) + uint32_t(f1 == a || f1 == b || f1 == c) +
+                             uint32_t(f2 == a || f2 == b || f2 == c) + uint32_t(f3 == a || f3 == b || f3 == c);
+        if (hit != 3) continue;
+        x = f0 ^ f1 ^ f2 ^ f3 ^ a ^ b ^ c;
+        if (has3(v.hs3, a, b, x) || has3(v.hs3, a, c, x) || has3(v.hs3, b, c, x)) continue;
+        quad = 1;
+      }
+      // fill-in of e u {x}
+      if (slot <= 0) acv = has3(v.hs3, a, c, x);
+      if (slot <= 1) bcv = has3(v.hs3, b, c, x);
+      if (slot < 3) {
+        uint32_t s0 = a, s1 = b, s2 = c, s3 = x;
+        // ascending 4-tuple for the 4-node probe
+        if (s3 < s2) { const uint32_t t = s2; s2 = s3; s3 = t; }
+        if (s2 < s1) { const uint32_t t = s1; s1 = s2; s2 = t; }
+        if (s1 < s0) { const uint32_t t = s0; s0 = s1; s1 = t; }
+        quad = set128_has(v.hs4, key4(s0, s1, s2, s3));
+      }
+      const uint32_t av = has2(v.hs2, a, x), bv = has2(v.hs2, b, x), cv = has2(v.hs2, c, x);
+      const uint32_t combo = av | (bv << 1) | (cv << 2);
+      dn1 += combo == 1;
+      dn2 += combo == 2;
+      dn3 += combo == 3;
+      dn4 += combo == 4;
+      dn5 += combo == 5;
+      dn6 += combo == 6;
+      dn7 += combo == 7;
+      if (quad) continue;   // a 4-node hyperedge: counted on its own, or larger than a sampled 3-node one
+      if (OWN) {
+        // e must be the smallest 3-node hyperedge of the set
+        uint32_t t0 = a, t1 = b, t2 = x;
+        bool owned = true;
+        if (abv) { sort3(t0, t1, t2); owned = owned && !tri_less(t0, t1, t2, a, b, c); }
+        t0 = a; t1 = c; t2 = x;
+        if (acv) { sort3(t0, t1, t2); owned = owned && !tri_less(t0, t1, t2, a, b, c); }
+        t0 = b; t1 = c; t2 = x;
+        if (bcv) { sort3(t0, t1, t2); owned = owned && !tri_less(t0, t1, t2, a, b, c); }
+        if (!owned) continue;
+      }
+      const uint32_t pat = base_p | (av << 4) | (bv << 5) | (abv << 6) | (cv << 7) | (acv << 8) | (bcv << 9);
+      atomicAdd(&h_main[lut[pat]], 1ull);
+      if (OWN) {
+        const uint8_t g = lut[pat & kPairBits4];
+        if (g != 0xFF) atomicAdd(&h_sub[g], 1ull);
+      }
+    }
+  }
+  dn1 = wave_sum_u32(dn1);
+  dn2 = wave_sum_u32(dn2);
+  dn3 = wave_sum_u32(dn3);
+  dn4 = wave_sum_u32(dn4);
+  dn5 = wave_sum_u32(dn5);
+  dn6 = wave_sum_u32(dn6);
+  dn7 = wave_sum_u32(dn7);
+  if (lane == 0) {
+    // inclusion-exclusion over N(a), N(b), N(c) with the members of e removed
+    const uint32_t sa = da - pab - pac, sb = db - pab - pbc, sc = dc - pac - pbc;
+    const uint32_t iab = cab - pac * pbc, iac = cac - pab * pbc, ibc = cbc - pab * pac;
+    uint32_t n[8];
+    n[7] = tri;
+    n[3] = iab - tri;
+    n[5] = iac - tri;
+    n[6] = ibc - tri;
+    n[1] = sa - n[3] - n[5] - n[7];
+    n[2] = sb - n[3] - n[6] - n[7];
+    n[4] = sc - n[5] - n[6] - n[7];
+    n[1] -= dn1;
+    n[2] -= dn2;
+    n[3] -= dn3;
+    n[4] -= dn4;
+    n[5] -= dn5;
+    n[6] -= dn6;
+    n[7] -= dn7;
+#pragma unroll
+    for (uint32_t cmb = 1; cmb < 8; ++cmb) {
+      if (!n[cmb]) continue;
+      const uint32_t pat = base_p | ((cmb & 1u) << 4) | (((cmb >> 1) & 1u) << 5) | ((cmb >> 2) << 7);
+      atomicAdd(&h_main[lut[pat]], (unsigned long long)n[cmb]);
+      if (OWN) {
+        const uint8_t g = lut[pat & kPairBits4];
+        if (g != 0xFF) atomicAdd(&h_sub[g], (unsigned long long)n[cmb]);
+      }
+    }
+  }
+}
+
+}  // namespace hm

@@ -367,4 +367,24 @@ int fill_u64(unsigned long long* p, unsigned long long value, uint64_t n, hipStr
   return fill_impl<unsigned long long>(p, value, n, st);
 }
 
+__global__ void k_max_u32(const uint32_t* __restrict__ v, uint64_t n, uint32_t* out) {
+  uint32_t m = 0;
+  for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += uint64_t(gridDim.x) * blockDim.x)
+    m = v[i] > m ? v[i] : m;
+  for (int d = kWave / 2; d > 0; d >>= 1) {
+    const uint32_t o = __shfl_xor(m, d, kWave);
+    m = o > m ? o : m;
+  }
+  if ((threadIdx.x & (kWave - 1)) == 0 && m) atomicMax(out, m);
+}
+
+int max_u32(const uint32_t* v, uint64_t n, uint32_t* out, hipStream_t st) {
+  if (!n) return HM_OK;
+  uint64_t g = (n + 255) / 256;
+  if (g > 1024) g = 1024;
+  k_max_u32<<<unsigned(g), 256, 0, st>>>(v, n, out);
+  HM_HIP(hipGetLastError());
+  return HM_OK;
+}
+
 }  // namespace hm

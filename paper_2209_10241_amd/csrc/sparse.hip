@@ -1,0 +1,408 @@
+// Exact order-3 and order-4 counts on hypergraphs without adjacency bit rows
+// (Algorithms 2 and 3, Section 4.2), sized for graphs with millions of
+// hyperedges and heavy-tailed degrees.
+//
+// The generators and ownership rules are those of the bit-row path:
+//   (a) every k-node hyperedge, classified by fill-in;
+//   (b) order 4: every 3-node hyperedge with each fourth node, counted per
+//       pairwise combination by inclusion-exclusion (hm_sparse.h);
+//   (c) sets connected through pairs only: never enumerated.  The number of
+//       connected k-node sets of the pairwise graph G2 per induced shape
+//       follows from non-induced subgraph counts: 3-stars sum C(d,3),
+//       3-paths sum over edges (d_u-1)(d_v-1) - 3T, paws sum t_v (d_v-2),
+//       diamonds sum over edges C(t_e,2), 4-cycles and 4-cliques by
+//       degree-ordered enumeration, inverted through the matrix of how often
+//       each shape contains another; then the sets that (a) or (b) own are
+//       subtracted by shape.
+// Degree order: x precedes y when (deg x, x) < (deg y, y); a node's
+// neighbours that follow it number at most sqrt(2 |E2|).
+#include <algorithm>
+#include <vector>
+
+#include "hm_sparse.h"
+
+namespace hm {
+namespace {
+
+enum : int { kAccT3 = 0, kAccDiamond, kAccP4, kAccStar, kAccPaw, kAccC4, kAccK4, kAccWedge, kAccN };
+
+__device__ inline bool rank_less(const View& v, uint32_t x, uint32_t y) {
+  const uint32_t dx = deg2_of(v, x), dy = deg2_of(v, y);
+  return dx < dy || (dx == dy && x < y);
+}
+
+// sum of x over the workgroup, added to *out by one thread
+__device__ inline void block_add(unsigned long long x, unsigned long long* out) {
+  __shared__ unsigned long long part[kWavesPerBlock];
+  x = wave_sum(x);
+  const int wv = threadIdx.x / kWave;
+  if ((threadIdx.x & (kWave - 1)) == 0) part[wv] = x;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long s = 0;
+    for (int i = 0; i < kWavesPerBlock; ++i) s += part[i];
+    if (s) atomicAdd(out, s);
+  }
+  __syncthreads();
+}
+
+// Triangles on each pair {a, b} of G2: t_e = |N(a) n N(b)| over the smaller
+// row.  tv[x] collects sum of t_e over the pairs at x (= 2 t_x).
+__global__ void __launch_bounds__(kThreads) k_sp_edge_tri(View v, uint64_t n2, uint32_t* __restrict__ tri_e,
+                                                          unsigned long long* __restrict__ tv,
+                                                          unsigned long long* __restrict__ acc) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const uint64_t wave = uint64_t(blockIdx.x) * kWavesPerBlock + threadIdx.x / kWave;
+  const uint64_t n_waves = uint64_t(gridDim.x) * kWavesPerBlock;
+  unsigned long long st = 0, sd = 0, sp = 0;
+  for (uint64_t e = wave; e < n2; e += n_waves) {
+    const uint32_t a = v.e2[2 * e], b = v.e2[2 * e + 1];
+    const uint32_t da = deg2_of(v, a), db = deg2_of(v, b);
+    const uint32_t s = da <= db ? a : b, o = da <= db ? b : a;
+    const uint32_t t = row_count(v, s, o);
+    if (lane == 0) {
+      tri_e[e] = t;
+      if (t) {
+        atomicAdd(&tv[a], (unsigned long long)t);
+        atomicAdd(&tv[b], (unsigned long long)t);
+      }
+      st += t;
+      sd += (unsigned long long)t * (t - 1) / 2;
+      sp += (unsigned long long)(da - 1) * (db - 1);
+    }
+  }
+  block_add(st, acc + kAccT3);
+  block_add(sd, acc + kAccDiamond);
+  block_add(sp, acc + kAccP4);
+}
+
+// Per node: C(d,3) (3-stars), C(d,2) (wedges), t_x (d - 2) (paws).
+__global__ void __launch_bounds__(kThreads) k_sp_nodes(View v, const unsigned long long* __restrict__ tv,
+                                                       unsigned long long* __restrict__ acc) {
+  unsigned long long s3 = 0, s2 = 0, sp = 0;
+  for (uint32_t x = blockIdx.x * kThreads + threadIdx.x; x < v.N; x += gridDim.x * kThreads) {
+    const unsigned long long d = deg2_of(v, x);
+    if (d >= 2) {
+      s2 += d * (d - 1) / 2;
+      sp += (tv[x] / 2) * (d - 2);
+    }
+    if (d >= 3) s3 += d * (d - 1) / 2 * (d - 2) / 3;
+  }
+  block_add(s3, acc + kAccStar);
+  block_add(s2, acc + kAccWedge);
+  block_add(sp, acc + kAccPaw);
+}
+
+// 4-cycles: for the cycle's top node u in degree order and the node w
+// opposite it, the middle nodes are common neighbours of u and w that precede
+// u; cnt[w] counts them and the cycles through (u, w) are C(cnt[w], 2).  One
+// workgroup per u; the row of u is taken 256 neighbours at a time and the
+// rows of those that precede u are walked as one flat range.  cnt and the
+// list of touched w are private to the workgroup (N entries each, zero
+// between nodes).
+__global__ void __launch_bounds__(kThreads) k_sp_c4(View v, uint32_t* __restrict__ cnt_all,
+                                                    uint32_t* __restrict__ touched_all,
+                                                    unsigned long long* __restrict__ acc) {
+  __shared__ uint32_t pre[kThreads + 1];
+  __shared__ uint32_t vv[kThreads];
+  __shared__ uint32_t wave_tot[kWavesPerBlock];
+  __shared__ uint32_t n_touched;
+  uint32_t* cnt = cnt_all + uint64_t(blockIdx.x) * v.N;
+  uint32_t* touched = touched_all + uint64_t(blockIdx.x) * v.N;
+  const uint32_t tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
+  unsigned long long total = 0;
+  for (uint32_t u = blockIdx.x; u < v.N; u += gridDim.x) {
+    const uint32_t ub = v.g2_off[u], ue = v.g2_off[u + 1];
+    if (ue - ub < 2) continue;
+    if (tid == 0) n_touched = 0;
+    for (uint32_t c0 = ub; c0 < ue; c0 += kThreads) {
+      uint32_t x = 0, len = 0;
+      if (c0 + tid < ue) {
+        x = v.g2_adj[c0 + tid];
+        if (rank_less(v, x, u)) len = deg2_of(v, x);
+      }
+      uint32_t wtot;
+      uint32_t off = wave_exclusive_scan(len, &wtot);
+      if (lane == 0) wave_tot[wv] = wtot;
+      __syncthreads();
+      for (uint32_t q = 0; q < wv; ++q) off += wave_tot[q];
+      vv[tid] = x;
+      pre[tid] = off;
+      if (tid == kThreads - 1) pre[kThreads] = off + len;
+      __syncthreads();
+      const uint32_t work = pre[kThreads];
+      for (uint32_t t = tid; t < work; t += kThreads) {
+        uint32_t lo = 0, hi = kThreads;   // pre[lo] <= t < pre[hi]
+        while (hi - lo > 1) {
+          const uint32_t m = (lo + hi) >> 1;
+          if (pre[m] <= t) lo = m; else hi = m;
+        }
+        const uint32_t y = vv[lo];
+        const uint32_t w = v.g2_adj[v.g2_off[y] + (t - pre[lo])];
+        if (w == u || !rank_less(v, w, u)) continue;
+        if (atomicAdd(&cnt[w], 1u) == 0u) touched[atomicAdd(&n_touched, 1u)] = w;
+      }
+      __syncthreads();
+    }
+    const uint32_t nt = n_touched;
+    for (uint32_t i = tid; i < nt; i += kThreads) {
+      const unsigned long long c = atomicExch(&cnt[touched[i]], 0u);
+      total += c * (c - 1) / 2;
+    }
+    __syncthreads();
+  }
+  block_add(total, acc + kAccC4);
+}
+
+// Neighbours that follow each node in degree order.
+__global__ void k_sp_outdeg(View v, uint32_t* __restrict__ outdeg) {
+  for (uint32_t x = blockIdx.x * blockDim.x + threadIdx.x; x < v.N; x += gridDim.x * blockDim.x) {
+    uint32_t n = 0;
+    for (uint32_t p = v.g2_off[x]; p < v.g2_off[x + 1]; ++p) n += rank_less(v, x, v.g2_adj[p]);
+    outdeg[x] = n;
+  }
+}
+
+// 4-cliques: for each pair {lo, hi} of G2 (lo before hi in degree order),
+// W = common neighbours after hi; every pair of W joined by a pair of G2
+// closes one 4-clique, found once at its first two nodes.  One wavefront per
+// pair; W goes to a per-wavefront list of cap entries.
+__global__ void __launch_bounds__(kThreads) k_sp_k4(View v, uint64_t n2, uint32_t cap, uint32_t* __restrict__ wlist,
+                                                    unsigned long long* __restrict__ acc) {
+  const uint32_t lane = threadIdx.x & (kWave - 1);
+  const uint64_t wave = uint64_t(blockIdx.x) * kWavesPerBlock + threadIdx.x / kWave;
+  const uint64_t n_waves = uint64_t(gridDim.x) * kWavesPerBlock;
+  uint32_t* W = wlist + wave * cap;
+  unsigned long long total = 0;
+  for (uint64_t e = wave; e < n2; e += n_waves) {
+    uint32_t lo = v.e2[2 * e], hi = v.e2[2 * e + 1];
+    if (rank_less(v, hi, lo)) {
+      const uint32_t t = lo;
+      lo = hi;
+      hi = t;
+    }
+    uint32_t nw = 0;
+    for (uint32_t p0 = v.g2_off[lo]; p0 < v.g2_off[lo + 1]; p0 += kWave) {
+      const uint32_t p = p0 + lane;
+      bool keep = false;
+      uint32_t w = 0;
+      if (p < v.g2_off[lo + 1]) {
+        w = v.g2_adj[p];
+        keep = rank_less(v, hi, w) && has2(v.hs2, hi, w);
+      }
+      const unsigned long long m = __ballot(keep);
+      if (keep) W[nw + __popcll(m & ((1ull << lane) - 1ull))] = w;
+      nw += uint32_t(__popcll(m));
+    }
+    wave_sync();
+    uint32_t c = 0;
+    for (uint32_t i = 0; i + 1 < nw; ++i) {
+      const uint32_t wi = W[i];
+      for (uint32_t j = i + 1 + lane; j < nw; j += kWave) c += has2(v.hs2, wi, W[j]);
+    }
+    total += wave_sum_u32(c);
+    wave_sync();
+  }
+  if (lane == 0) atomicAdd(acc + kAccK4, total);
+}
+
+// (b) at order 4 without bit rows: one wavefront per 3-node hyperedge.
+__global__ void __launch_bounds__(kThreads) k_sp_b4(View v, PairLinks pl, uint64_t n3, const uint8_t* __restrict__ lut_g,
+                                                    unsigned long long* __restrict__ hist) {
+  __shared__ uint8_t lut[2048];
+  __shared__ unsigned long long h_main[256], h_sub[256];
+  load_lut(lut, lut_g, 2048);
+  h_main[threadIdx.x] = 0;
+  h_sub[threadIdx.x] = 0;
+  __syncthreads();
+  const uint64_t wave = uint64_t(blockIdx.x) * kWavesPerBlock + threadIdx.x / kWave;
+  const uint64_t n_waves = uint64_t(gridDim.x) * kWavesPerBlock;
+  for (uint64_t i = wave; i < n3; i += n_waves)
+    b4_sparse<true>(v, pl, v.e3[3 * i], v.e3[3 * i + 1], v.e3[3 * i + 2], lut, h_main, h_sub);
+  __syncthreads();
+  flush(h_main, hist + kMain, 256);
+  flush(h_sub, hist + kSub, 256);
+}
+
+// Induced shape counts from the non-induced ones, into the G2 region.
+struct ShapeClasses {
+  int k3_path, k3_triangle;
+  int path, star, cycle, paw, diamond, clique;
+};
+
+__global__ void k_sp_shapes(const unsigned long long* __restrict__ acc, int k, ShapeClasses cls,
+                            unsigned long long* __restrict__ hist) {
+  if (threadIdx.x != 0) return;
+  const unsigned long long T = acc[kAccT3] / 3;
+  if (k == 3) {
+    hist[kG2 + cls.k3_triangle] = T;
+    hist[kG2 + cls.k3_path] = acc[kAccWedge] - 3 * T;
+    return;
+  }
+  const unsigned long long k4 = acc[kAccK4];
+  const unsigned long long dia = acc[kAccDiamond] - 6 * k4;
+  const unsigned long long cyc = acc[kAccC4] - dia - 3 * k4;
+  const unsigned long long paw = acc[kAccPaw] - 4 * dia - 12 * k4;
+  const unsigned long long star = acc[kAccStar] - paw - 2 * dia - 4 * k4;
+  const unsigned long long path = (acc[kAccP4] - 3 * T) - 4 * cyc - 2 * paw - 6 * dia - 12 * k4;
+  hist[kG2 + cls.clique] = k4;
+  hist[kG2 + cls.diamond] = dia;
+  hist[kG2 + cls.cycle] = cyc;
+  hist[kG2 + cls.paw] = paw;
+  hist[kG2 + cls.star] = star;
+  hist[kG2 + cls.path] = path;
+}
+
+__global__ void k_pair_link_keys(const uint32_t* __restrict__ e3, uint64_t n3, unsigned long long* __restrict__ keys,
+                                 uint32_t* __restrict__ edge) {
+  for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n3; i += uint64_t(gridDim.x) * blockDim.x) {
+    const unsigned long long a = e3[3 * i], b = e3[3 * i + 1], c = e3[3 * i + 2];
+    keys[3 * i] = (a << 32) | b;
+    keys[3 * i + 1] = (a << 32) | c;
+    keys[3 * i + 2] = (b << 32) | c;
+    edge[3 * i] = edge[3 * i + 1] = edge[3 * i + 2] = uint32_t(i);
+  }
+}
+
+struct Scratch {
+  std::vector<void*> ptrs;
+  ~Scratch() {
+    for (void* p : ptrs) dfree(p);
+  }
+  template <typename T>
+  int get(T** p, uint64_t n) {
+    void* q = nullptr;
+    HM_TRY(dalloc(&q, size_t(n ? n : 1) * sizeof(T)));
+    ptrs.push_back(q);
+    *p = static_cast<T*>(q);
+    return HM_OK;
+  }
+};
+
+unsigned grid_cap(uint64_t items, uint64_t per_block, unsigned cap) {
+  uint64_t g = (items + per_block - 1) / per_block;
+  return unsigned(std::max<uint64_t>(1, std::min<uint64_t>(g, cap)));
+}
+
+}  // namespace
+
+// The pair -> 3-node hyperedge index of H, built on first use.
+int ensure_pair_links(hm_graph* H, hipStream_t st) {
+  if (H->pl_keys || H->n_by_size[3] == 0) return HM_OK;
+  const uint64_t n = 3 * H->n_by_size[3];
+  void *k = nullptr, *e = nullptr, *kt = nullptr, *et = nullptr;
+  HM_TRY(dalloc(&k, n * sizeof(unsigned long long)));
+  int rc = dalloc(&e, n * sizeof(uint32_t));
+  if (rc == HM_OK) rc = dalloc(&kt, n * sizeof(unsigned long long));
+  if (rc == HM_OK) rc = dalloc(&et, n * sizeof(uint32_t));
+  if (rc == HM_OK) {
+    k_pair_link_keys<<<grid_cap(H->n_by_size[3], 256, 4096), 256, 0, st>>>(
+        H->e3, H->n_by_size[3], static_cast<unsigned long long*>(k), static_cast<uint32_t*>(e));
+    if (hipGetLastError() != hipSuccess) rc = HM_EDEVICE;
+  }
+  int bits = 1;
+  while (bits < 32 && (1ull << bits) < H->n_nodes) ++bits;
+  if (rc == HM_OK)
+    rc = radix_sort_pairs(static_cast<unsigned long long*>(k), static_cast<uint32_t*>(e),
+                          static_cast<unsigned long long*>(kt), static_cast<uint32_t*>(et), n, 32 + bits, st);
+  if (rc == HM_OK && hipStreamSynchronize(st) != hipSuccess) rc = HM_EDEVICE;
+  dfree(kt);
+  dfree(et);
+  if (rc != HM_OK) {
+    dfree(k);
+    dfree(e);
+    return rc;
+  }
+  H->pl_keys = static_cast<unsigned long long*>(k);
+  H->pl_edge = static_cast<uint32_t*>(e);
+  return HM_OK;
+}
+
+PairLinks pair_links_of(const hm_graph* H) {
+  PairLinks pl;
+  pl.keys = H->pl_keys;
+  pl.edge = H->pl_edge;
+  pl.n = H->pl_keys ? 3 * H->n_by_size[3] : 0;
+  return pl;
+}
+
+// Fills the main, sub and G2 regions of H->hist (zeroed by the caller) except
+// case (a), which the caller counts.
+int count_sparse(const hm_graph* H, int k, hipStream_t st) {
+  const uint8_t *lut4 = nullptr, *lut3 = nullptr;
+  HM_TRY(device_luts(H->device, &lut4, &lut3));
+  const View v = view_of(H);
+  const uint64_t n2 = H->n_by_size[2], n3 = H->n_by_size[3];
+  Scratch tmp;
+  unsigned long long *acc = nullptr, *tv = nullptr;
+  uint32_t* tri_e = nullptr;
+  HM_TRY(tmp.get(&acc, kAccN));
+  HM_TRY(tmp.get(&tv, H->n_nodes));
+  HM_TRY(tmp.get(&tri_e, n2));
+  HM_TRY(fill_u64(acc, 0, kAccN, st));
+  HM_TRY(fill_u64(tv, 0, H->n_nodes, st));
+  if (n2) {
+    ProfileScope ps("k_sp_edge_tri", st);
+    k_sp_edge_tri<<<grid_cap(n2, kWavesPerBlock, 2048), kThreads, 0, st>>>(v, n2, tri_e, tv, acc);
+  }
+  {
+    ProfileScope ps("k_sp_nodes", st);
+    k_sp_nodes<<<grid_cap(H->n_nodes, kThreads, 1024), kThreads, 0, st>>>(v, tv, acc);
+  }
+  HM_HIP(hipGetLastError());
+  const ClassTables& t = class_tables();
+  ShapeClasses cls;
+  // representative pair patterns (local nodes 0..3; bits: 01=0, 02=1, 12=2, 03=4, 13=5, 23=7)
+  cls.k3_path = t.lut3[0x3];       // 01, 02
+  cls.k3_triangle = t.lut3[0x7];   // 01, 02, 12
+  cls.path = t.lut4[(1u << 0) | (1u << 2) | (1u << 7)];
+  cls.star = t.lut4[(1u << 0) | (1u << 1) | (1u << 4)];
+  cls.cycle = t.lut4[(1u << 0) | (1u << 2) | (1u << 7) | (1u << 4)];
+  cls.paw = t.lut4[(1u << 0) | (1u << 1) | (1u << 2) | (1u << 4)];
+  cls.diamond = t.lut4[(1u << 0) | (1u << 1) | (1u << 2) | (1u << 4) | (1u << 5)];
+  cls.clique = t.lut4[kPairBits4];
+  if (k == 4 && n2) {
+    // 4-cycles
+    // workgroups, each with 8 bytes of counters per node: at most about 1 GiB
+    const unsigned g = grid_cap(H->n_nodes, 1, unsigned(std::max<uint64_t>(64, std::min<uint64_t>(512, (1ull << 27) / std::max<uint32_t>(H->n_nodes, 1)))));
+    uint32_t *cnt = nullptr, *touched = nullptr;
+    HM_TRY(tmp.get(&cnt, uint64_t(g) * H->n_nodes));
+    HM_TRY(tmp.get(&touched, uint64_t(g) * H->n_nodes));
+    HM_TRY(fill_u32(cnt, 0, uint64_t(g) * H->n_nodes, st));
+    {
+      ProfileScope ps("k_sp_c4", st);
+      k_sp_c4<<<g, kThreads, 0, st>>>(v, cnt, touched, acc);
+    }
+    // 4-cliques
+    uint32_t *outdeg = nullptr, *dmax = nullptr;
+    HM_TRY(tmp.get(&outdeg, H->n_nodes));
+    HM_TRY(tmp.get(&dmax, 1));
+    HM_TRY(fill_u32(dmax, 0, 1, st));
+    k_sp_outdeg<<<grid_cap(H->n_nodes, 256, 1024), 256, 0, st>>>(v, outdeg);
+    HM_TRY(max_u32(outdeg, H->n_nodes, dmax, st));
+    uint32_t cap = 0;
+    HM_HIP(hipMemcpyAsync(&cap, dmax, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    HM_HIP(hipStreamSynchronize(st));
+    const unsigned gk = grid_cap(n2, kWavesPerBlock, 1024);
+    uint32_t* wlist = nullptr;
+    HM_TRY(tmp.get(&wlist, uint64_t(gk) * kWavesPerBlock * std::max<uint32_t>(cap, 1)));
+    {
+      ProfileScope ps("k_sp_k4", st);
+      k_sp_k4<<<gk, kThreads, 0, st>>>(v, n2, std::max<uint32_t>(cap, 1), wlist, acc);
+    }
+    HM_HIP(hipGetLastError());
+  }
+  if (k == 4 && n3) {
+    HM_TRY(ensure_pair_links(const_cast<hm_graph*>(H), st));
+    ProfileScope ps("k_sp_b4", st);
+    k_sp_b4<<<grid_cap(n3, kWavesPerBlock, 2048), kThreads, 0, st>>>(v, pair_links_of(H), n3, lut4, H->hist);
+    HM_HIP(hipGetLastError());
+  }
+  k_sp_shapes<<<1, 64, 0, st>>>(acc, k, cls, H->hist);
+  HM_HIP(hipGetLastError());
+  // the scratch is released when the work is done
+  HM_HIP(hipStreamSynchronize(st));
+  return HM_OK;
+}
+
+}  // namespace hm

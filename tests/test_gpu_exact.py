@@ -84,6 +84,25 @@ def test_facetoface_order4_workload(hm, bit_rows):
     assert np.array_equal(_gpu_counts(hm, h, 4, bit_rows), _golden("facetoface_N400_E30000", 4))
 
 
+@pytest.mark.parametrize("bit_rows", [True, False], ids=["bits", "hash"])
+def test_communication_scaled_workload(hm, bit_rows):
+    """Heavy-tailed degrees (communication recipe at 0.4% of its size), stored oracle counts."""
+    h = W.scaled_communication(0.004, 0)
+    assert np.array_equal(_gpu_counts(hm, h, 4, bit_rows), _golden("communication_scaled_0.004", 4))
+
+
+@pytest.mark.parametrize("scale", [0.02, 0.05])
+def test_sparse_path_agrees_with_bit_rows(hm, scale):
+    """Larger heavy-tailed graphs: the counting formulas without bit rows and the
+    bit-row enumeration are independent routes to the same int64 counts."""
+    h = W.scaled_communication(scale, 1)
+    for k in (3, 4):
+        a = _gpu_counts(hm, h, k, True)
+        b = _gpu_counts(hm, h, k, False)
+        assert np.array_equal(a, b), (scale, k)
+        assert a.sum() > 0
+
+
 def test_facetoface_order4_relabelled(hm):
     h = W.cfg1_facetoface_k4(0)
     perm = np.random.default_rng(5).permutation(h.n_nodes)
