@@ -220,8 +220,8 @@ __global__ void k_pair_keys(const uint32_t* __restrict__ e2, uint64_t n, int bit
     const uint32_t a = e2[2 * i], b = e2[2 * i + 1];
     keys[2 * i] = ((unsigned long long)a << bits_per_node) | b;
     keys[2 * i + 1] = ((unsigned long long)b << bits_per_node) | a;
-    vals[2 * i] = 0;
-    vals[2 * i + 1] = 0;
+    vals[2 * i] = uint32_t(i);
+    vals[2 * i + 1] = uint32_t(i);
     atomicAdd(&deg[a], 1u);
     atomicAdd(&deg[b], 1u);
   }
@@ -476,7 +476,8 @@ int build(hm_graph* H, const uint32_t* members_in, const uint64_t* offsets_in, u
     uint32_t *vals, *vals_tmp, *deg, *dmax;
     HM_TRY(tmp.get(&keys, m));
     HM_TRY(tmp.get(&keys_tmp, m));
-    HM_TRY(tmp.get(&vals, m));
+    HM_TRY(owned(&H->g2_eid, m));
+    vals = H->g2_eid;
     HM_TRY(tmp.get(&vals_tmp, m));
     HM_TRY(tmp.get(&deg, H->n_nodes));
     HM_TRY(tmp.get(&dmax, 1));
@@ -529,6 +530,7 @@ void release(hm_graph* H) {
   dfree(H->hs4.slot);
   dfree(H->g2_off);
   dfree(H->g2_adj);
+  dfree(H->g2_eid);
   dfree(H->i3_off);
   dfree(H->i3_idx);
   dfree(H->i4_off);
@@ -538,6 +540,10 @@ void release(hm_graph* H) {
   dfree(H->sample_hist);
   dfree(H->pl_keys);
   dfree(H->pl_edge);
+  dfree(H->ns_tri);
+  dfree(H->ns_nbr);
+  dfree(H->ns_h3);
+  dfree(H->es);
   if (H->null_plan) destroy_null_plan(H->null_plan);
   H->null_plan = nullptr;
   if (H->proposal) destroy_proposal_cache(H->proposal);

@@ -181,6 +181,8 @@ void dfree(void* p);
 // into H->hist (case (a) is counted by the caller).
 int count_sparse(const hm_graph* H, int k, hipStream_t st);
 int ensure_pair_links(hm_graph* H, hipStream_t st);
+int ensure_node_stats(hm_graph* H, hipStream_t st);
+int ensure_edge_stats(hm_graph* H, hipStream_t st);
 
 struct NullPlan;
 void destroy_null_plan(NullPlan* p);
@@ -214,6 +216,7 @@ struct hm_graph {
   // pairwise graph: ascending neighbour rows
   uint32_t* g2_off = nullptr;   // n_nodes + 1
   uint32_t* g2_adj = nullptr;   // 2 * n2
+  uint32_t* g2_eid = nullptr;   // 2 * n2: position in e2 of the pair of each adjacency entry
   uint32_t max_deg2 = 0;
   // node -> incident 3-node hyperedges (indices into e3)
   uint32_t* i3_off = nullptr;
@@ -232,6 +235,15 @@ struct hm_graph {
   // of their hyperedge in e3; built on first use without bit rows
   unsigned long long* pl_keys = nullptr;
   uint32_t* pl_edge = nullptr;
+  // per node, built on first use without bit rows: triangles at the node, sum
+  // of its neighbours' degrees, its 3-node hyperedges by pairwise pattern (8)
+  unsigned long long* ns_tri = nullptr;
+  unsigned long long* ns_nbr = nullptr;
+  uint32_t* ns_h3 = nullptr;
+  // per pair of e2 (u < w), built on first use without bit rows, 6 x n2:
+  // triangles, 4-cliques and 4-cycles through it; over its common neighbours
+  // x: sum of t_{ux}, sum of t_{wx}, sum of deg x
+  unsigned long long* es = nullptr;
   // raw counters (256) and finished-workgroup ticket of the sampled counting
   // calls; zero between calls
   unsigned long long* sample_hist = nullptr;

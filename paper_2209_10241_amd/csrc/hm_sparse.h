@@ -82,104 +82,138 @@ __device__ void b4_sparse(const View& v, const PairLinks& pl, uint32_t a, uint32
   const uint32_t pab = has2(v.hs2, a, b), pac = has2(v.hs2, a, c), pbc = has2(v.hs2, b, c);
   const uint32_t base_p = pab | (pac << 1) | (pbc << 2) | (1u << 3);
   const uint32_t da = deg2_of(v, a), db = deg2_of(v, b), dc = deg2_of(v, c);
-  // intersections: the smallest row against the other two, then the smaller
-  // of the remaining two rows against the last
-  uint32_t cab, cac, cbc, tri;
+  // intersections, in one lane-strided range: the smallest row against the
+  // other two members, then the smaller of the remaining two rows against the
+  // last member
+  uint32_t r1, x1, y1, r2, x2;   // rows walked and the members they are probed against
   if (da <= db && da <= dc) {
-    row_probe(v, a, b, c, cab, cac, tri);
-    cbc = db <= dc ? row_count(v, b, c) : row_count(v, c, b);
+    r1 = a; x1 = b; y1 = c;
+    r2 = db <= dc ? b : c; x2 = db <= dc ? c : b;
   } else if (db <= dc) {
-    row_probe(v, b, a, c, cab, cbc, tri);
-    cac = da <= dc ? row_count(v, a, c) : row_count(v, c, a);
+    r1 = b; x1 = a; y1 = c;
+    r2 = da <= dc ? a : c; x2 = da <= dc ? c : a;
   } else {
-    row_probe(v, c, a, b, cac, cbc, tri);
-    cab = da <= db ? row_count(v, a, b) : row_count(v, b, a);
+    r1 = c; x1 = a; y1 = b;
+    r2 = da <= db ? a : b; x2 = da <= db ? b : a;
   }
-  // exceptional nodes, each once, by the first hyperedge that makes it one
-  // (slot 0..2: {a,b,v}, {a,c,v}, {b,c,v}; slot 3: {a,b,c,v}); per lane,
-  // the number of them in each pairwise combination
-  uint32_t dn1 = 0, dn2 = 0, dn3 = 0, dn4 = 0, dn5 = 0, dn6 = 0, dn7 = 0;
-  for (int slot = 0; slot < 4; ++slot) {
-    uint64_t lo = 0, hi = 0;
-    uint32_t q0 = 0, q1 = 0;   // the pair of this slot
-    if (slot < 3) {
-      q0 = slot < 2 ? a : b;
-      q1 = slot == 0 ? b : c;
-      const unsigned long long key = ((unsigned long long)q0 << 32) | q1;
-      lo = pl_lower(pl, key);
-      hi = pl_lower(pl, key + 1);
-    } else {
-      // 4-node hyperedges holding e, from the member with the fewest of them
-      const uint32_t fa = v.i4_off[a + 1] - v.i4_off[a], fb = v.i4_off[b + 1] - v.i4_off[b],
-                     fc = v.i4_off[c + 1] - v.i4_off[c];
-      const uint32_t s = (fa <= fb && fa <= fc) ? a : (fb <= fc ? b : c);
-      lo = v.i4_off[s];
-      hi = v.i4_off[s + 1];
-    }
-    for (uint64_t p = lo + lane; p < hi; p += kWave) {
-      uint32_t x;
-      uint32_t abv = 0, acv = 0, bcv = 0, quad = 0;
-      if (slot < 3) {
-        const uint32_t* f = v.e3 + 3ull * pl.edge[p];
-        x = f[0] ^ f[1] ^ f[2] ^ q0 ^ q1;
-        if (x == a || x == b || x == c) continue;   // e itself
-        if (slot == 0) {
-          abv = 1;
-        } else if (slot == 1) {
-          if (has3(v.hs3, a, b, x)) continue;
-          acv = 1;
-        } else {
-          if (has3(v.hs3, a, b, x) || has3(v.hs3, a, c, x)) continue;
-          bcv = 1;
-        }
+  uint32_t n1x = 0, n1y = 0, n1xy = 0, n2x = 0;
+  {
+    const uint32_t b1 = v.g2_off[r1], l1 = v.g2_off[r1 + 1] - b1;
+    const uint32_t b2 = v.g2_off[r2], l2 = v.g2_off[r2 + 1] - b2;
+    for (uint32_t t = lane; t < l1 + l2; t += kWave) {
+      if (t < l1) {
+        const uint32_t z = v.g2_adj[b1 + t];
+        const uint32_t hx = has2(v.hs2, x1, z), hy = has2(v.hs2, y1, z);
+        n1x += hx;
+        n1y += hy;
+        n1xy += hx & hy;
       } else {
-        const uint32_t* f = v.e4 + 4ull * v.i4_idx[p];
-        const uint32_t f0 = f[0], f1 = f[1], f2 = f[2], f3 = f[3];
-        const uint32_t hit = uint32_t(f0 == a || f0 == b || f0 == c) + uint32_t(f1 == a || f1 == b || f1 == c) +
-                             uint32_t(f2 == a || f2 == b || f2 == c) + uint32_t(f3 == a || f3 == b || f3 == c);
-        if (hit != 3) continue;
-        x = f0 ^ f1 ^ f2 ^ f3 ^ a ^ b ^ c;
-        if (has3(v.hs3, a, b, x) || has3(v.hs3, a, c, x) || has3(v.hs3, b, c, x)) continue;
-        quad = 1;
+        n2x += has2(v.hs2, x2, v.g2_adj[b2 + (t - l1)]);
       }
-      // fill-in of e u {x}
-      if (slot <= 0) acv = has3(v.hs3, a, c, x);
-      if (slot <= 1) bcv = has3(v.hs3, b, c, x);
-      if (slot < 3) {
-        uint32_t s0 = a, s1 = b, s2 = c, s3 = x;
-        // ascending 4-tuple for the 4-node probe
-        if (s3 < s2) { const uint32_t t = s2; s2 = s3; s3 = t; }
-        if (s2 < s1) { const uint32_t t = s1; s1 = s2; s2 = t; }
-        if (s1 < s0) { const uint32_t t = s0; s0 = s1; s1 = t; }
-        quad = set128_has(v.hs4, key4(s0, s1, s2, s3));
+    }
+    n1x = wave_sum_u32(n1x);
+    n1y = wave_sum_u32(n1y);
+    n1xy = wave_sum_u32(n1xy);
+    n2x = wave_sum_u32(n2x);
+  }
+  // codeg of each pair of e, and the triple intersection
+  const uint32_t tri = n1xy;
+  uint32_t cab, cac, cbc;
+  if (r1 == a) { cab = n1x; cac = n1y; cbc = n2x; }
+  else if (r1 == b) { cab = n1x; cbc = n1y; cac = n2x; }
+  else { cac = n1x; cbc = n1y; cab = n2x; }
+  // exceptional nodes, each once, by the first hyperedge that makes it one
+  // (slot 0..2: {a,b,v}, {a,c,v}, {b,c,v} through the pair index; slot 3:
+  // {a,b,c,v} from the member with the fewest 4-node hyperedges), all slots
+  // in one lane-strided range; per lane, the number of them in each pairwise
+  // combination
+  uint64_t lo[4], len[4];
+  for (int slot = 0; slot < 3; ++slot) {
+    const uint32_t q0 = slot < 2 ? a : b, q1 = slot == 0 ? b : c;
+    const unsigned long long key = ((unsigned long long)q0 << 32) | q1;
+    lo[slot] = pl_lower(pl, key);
+    len[slot] = pl_lower(pl, key + 1) - lo[slot];
+  }
+  {
+    const uint32_t fa = v.i4_off[a + 1] - v.i4_off[a], fb = v.i4_off[b + 1] - v.i4_off[b],
+                   fc = v.i4_off[c + 1] - v.i4_off[c];
+    const uint32_t m4 = (fa <= fb && fa <= fc) ? a : (fb <= fc ? b : c);
+    lo[3] = v.i4_off[m4];
+    len[3] = v.i4_off[m4 + 1] - lo[3];
+  }
+  const uint64_t total = len[0] + len[1] + len[2] + len[3];
+  uint32_t dn1 = 0, dn2 = 0, dn3 = 0, dn4 = 0, dn5 = 0, dn6 = 0, dn7 = 0;
+  for (uint64_t t = lane; t < total; t += kWave) {
+    int slot = 0;
+    uint64_t off = t;
+    while (off >= len[slot]) {
+      off -= len[slot];
+      ++slot;
+    }
+    const uint64_t p = lo[slot] + off;
+    uint32_t x;
+    uint32_t abv = 0, acv = 0, bcv = 0, quad = 0;
+    if (slot < 3) {
+      const uint32_t q0 = slot < 2 ? a : b, q1 = slot == 0 ? b : c;
+      const uint32_t* f = v.e3 + 3ull * pl.edge[p];
+      x = f[0] ^ f[1] ^ f[2] ^ q0 ^ q1;
+      if (x == a || x == b || x == c) continue;   // e itself
+      if (slot == 0) {
+        abv = 1;
+      } else if (slot == 1) {
+        if (has3(v.hs3, a, b, x)) continue;
+        acv = 1;
+      } else {
+        if (has3(v.hs3, a, b, x) || has3(v.hs3, a, c, x)) continue;
+        bcv = 1;
       }
-      const uint32_t av = has2(v.hs2, a, x), bv = has2(v.hs2, b, x), cv = has2(v.hs2, c, x);
-      const uint32_t combo = av | (bv << 1) | (cv << 2);
-      dn1 += combo == 1;
-      dn2 += combo == 2;
-      dn3 += combo == 3;
-      dn4 += combo == 4;
-      dn5 += combo == 5;
-      dn6 += combo == 6;
-      dn7 += combo == 7;
-      if (quad) continue;   // a 4-node hyperedge: counted on its own, or larger than a sampled 3-node one
-      if (OWN) {
-        // e must be the smallest 3-node hyperedge of the set
-        uint32_t t0 = a, t1 = b, t2 = x;
-        bool owned = true;
-        if (abv) { sort3(t0, t1, t2); owned = owned && !tri_less(t0, t1, t2, a, b, c); }
-        t0 = a; t1 = c; t2 = x;
-        if (acv) { sort3(t0, t1, t2); owned = owned && !tri_less(t0, t1, t2, a, b, c); }
-        t0 = b; t1 = c; t2 = x;
-        if (bcv) { sort3(t0, t1, t2); owned = owned && !tri_less(t0, t1, t2, a, b, c); }
-        if (!owned) continue;
-      }
-      const uint32_t pat = base_p | (av << 4) | (bv << 5) | (abv << 6) | (cv << 7) | (acv << 8) | (bcv << 9);
-      atomicAdd(&h_main[lut[pat]], 1ull);
-      if (OWN) {
-        const uint8_t g = lut[pat & kPairBits4];
-        if (g != 0xFF) atomicAdd(&h_sub[g], 1ull);
-      }
+    } else {
+      const uint32_t* f = v.e4 + 4ull * v.i4_idx[p];
+      const uint32_t f0 = f[0], f1 = f[1], f2 = f[2], f3 = f[3];
+      const uint32_t hit = uint32_t(f0 == a || f0 == b || f0 == c) + uint32_t(f1 == a || f1 == b || f1 == c) +
+                           uint32_t(f2 == a || f2 == b || f2 == c) + uint32_t(f3 == a || f3 == b || f3 == c);
+      if (hit != 3) continue;
+      x = f0 ^ f1 ^ f2 ^ f3 ^ a ^ b ^ c;
+      if (has3(v.hs3, a, b, x) || has3(v.hs3, a, c, x) || has3(v.hs3, b, c, x)) continue;
+      quad = 1;
+    }
+    // fill-in of e u {x}
+    if (slot <= 0) acv = has3(v.hs3, a, c, x);
+    if (slot <= 1) bcv = has3(v.hs3, b, c, x);
+    if (slot < 3) {
+      uint32_t s0 = a, s1 = b, s2 = c, s3 = x;
+      // ascending 4-tuple for the 4-node probe
+      if (s3 < s2) { const uint32_t tt = s2; s2 = s3; s3 = tt; }
+      if (s2 < s1) { const uint32_t tt = s1; s1 = s2; s2 = tt; }
+      if (s1 < s0) { const uint32_t tt = s0; s0 = s1; s1 = tt; }
+      quad = set128_has(v.hs4, key4(s0, s1, s2, s3));
+    }
+    const uint32_t av = has2(v.hs2, a, x), bv = has2(v.hs2, b, x), cv = has2(v.hs2, c, x);
+    const uint32_t combo = av | (bv << 1) | (cv << 2);
+    dn1 += combo == 1;
+    dn2 += combo == 2;
+    dn3 += combo == 3;
+    dn4 += combo == 4;
+    dn5 += combo == 5;
+    dn6 += combo == 6;
+    dn7 += combo == 7;
+    if (quad) continue;   // a 4-node hyperedge: counted on its own, or larger than a sampled 3-node one
+    if (OWN) {
+      // e must be the smallest 3-node hyperedge of the set
+      uint32_t t0 = a, t1 = b, t2 = x;
+      bool owned = true;
+      if (abv) { sort3(t0, t1, t2); owned = owned && !tri_less(t0, t1, t2, a, b, c); }
+      t0 = a; t1 = c; t2 = x;
+      if (acv) { sort3(t0, t1, t2); owned = owned && !tri_less(t0, t1, t2, a, b, c); }
+      t0 = b; t1 = c; t2 = x;
+      if (bcv) { sort3(t0, t1, t2); owned = owned && !tri_less(t0, t1, t2, a, b, c); }
+      if (!owned) continue;
+    }
+    const uint32_t pat = base_p | (av << 4) | (bv << 5) | (abv << 6) | (cv << 7) | (acv << 8) | (bcv << 9);
+    atomicAdd(&h_main[lut[pat]], 1ull);
+    if (OWN) {
+      const uint8_t g = lut[pat & kPairBits4];
+      if (g != 0xFF) atomicAdd(&h_sub[g], 1ull);
     }
   }
   dn1 = wave_sum_u32(dn1);

@@ -10,7 +10,7 @@
 // with mc = maxcard(m), formed in fp64 and rounded once to fp32.
 #include <cmath>
 
-#include "hm_items.h"
+#include "hm_sparse.h"
 
 namespace hm {
 namespace {
@@ -74,8 +74,9 @@ __device__ void sample_j4(const View& v, const Draws& d, uint32_t part, uint32_t
 // j = 3 at order 4: the neighbourhood of the sampled 3-node hyperedge.  One
 // wavefront per sample.
 template <bool BITS>
-__device__ void sample_j3_k4(const View& v, const Draws& d, uint32_t part, uint32_t n_parts, B4Scratch* scratch,
-                             const uint8_t* lut, unsigned long long* h_lds, unsigned long long* rows) {
+__device__ void sample_j3_k4(const View& v, const PairLinks& pl, const Draws& d, uint32_t part, uint32_t n_parts,
+                             B4Scratch* scratch, const uint8_t* lut, unsigned long long* h_lds,
+                             unsigned long long* rows) {
   const int wv = threadIdx.x / kWave;
   for (uint64_t s = uint64_t(part) * kWavesPerBlock + wv; s < d.S[3]; s += uint64_t(n_parts) * kWavesPerBlock) {
     const uint64_t i = d.at(3, s);
@@ -85,85 +86,336 @@ __device__ void sample_j3_k4(const View& v, const Draws& d, uint32_t part, uint3
       b4_edge_bits<false>(a, b, c, v.e3, v.e4, v.i3_off, v.i3_idx, v.i4_off, v.i4_idx, v.bits, v.W, scratch[wv], lut,
                           row_or(rows, s, h_lds), nullptr);
     else
-      b4_edge_hash<false>(a, b, c, v.e3, v.g2_off, v.g2_adj, v.i3_off, v.i3_idx, v.hs2, v.hs3, v.hs4, lut,
-                          row_or(rows, s, h_lds), nullptr);
+      b4_sparse<false>(v, pl, a, b, c, lut, row_or(rows, s, h_lds), nullptr);
   }
 }
 
-// Row-major index of the pair (p < q) among n items: row p starts at
-// p*n - p*(p+1)/2.
-__device__ inline void pair_from_index(uint64_t t, uint64_t n, uint32_t& p, uint32_t& q) {
-  const double b = double(2 * n - 1);
-  double r = (b - sqrt(b * b - 8.0 * double(t))) * 0.5;
-  uint64_t pp = r < 0.0 ? 0 : uint64_t(r);
-  if (pp > n - 2) pp = n - 2;
-  auto start = [n](uint64_t x) { return x * n - x * (x + 1) / 2; };
-  while (pp > 0 && start(pp) > t) --pp;
-  while (pp + 1 < n - 1 && start(pp + 1) <= t) ++pp;
-  p = uint32_t(pp);
-  q = uint32_t(t - start(pp) + pp + 1);
-}
-
-// j = 2 at order 4 without bit rows: the sampled pair e = {u, w}; the other
-// two nodes x, y make e u {x, y} connected through pairs (a larger hyperedge
-// would exceed e).  L lists the neighbours of u then those of w; a position
-// is valid when its node is neither u nor w and, for w's part, not also a
-// neighbour of u, so A = the valid nodes, each once.  Either both x and y lie
-// in A (a pair of valid positions p < q) or x lies in A and y is a neighbour
-// of x outside A u e.  One workgroup per sample.
 __device__ inline uint32_t nodeL(const uint32_t* g2_adj, uint32_t ub, uint32_t du, uint32_t wb, uint32_t p) {
   return p < du ? g2_adj[ub + p] : g2_adj[wb + (p - du)];
 }
 
-__device__ inline void j2_candidate(const View& v, uint32_t u, uint32_t w, uint32_t x, uint32_t y,
-                                    const uint8_t* lut, unsigned long long* h) {
-  if (has3(v.hs3, u, w, x) || has3(v.hs3, u, w, y) || has3(v.hs3, u, x, y) || has3(v.hs3, w, x, y)) return;
-  uint32_t q[4] = {u, w, x, y};
-  for (int i = 1; i < 4; ++i) {
-    const uint32_t k = q[i];
-    int j = i - 1;
-    while (j >= 0 && q[j] > k) { q[j + 1] = q[j]; --j; }
-    q[j + 1] = k;
+// Per-node statistics for the pair sampler without bit rows.
+struct NodeStats {
+  const unsigned long long* tri;   // triangles at the node
+  const unsigned long long* nbr;   // sum of the neighbours' degrees
+  const uint32_t* h3;              // 3-node hyperedges {x, y, z} at x by (x~y, x~z, y~z), y < z
+};
+
+// j = 2 at order 4 without bit rows, for the sampled pair e = {s, o}, s the
+// end of smaller degree.  The kept sets are those of the bit-row version
+// (below): e u {x, y} with x, y outside X = e u T, T = {t : {s,o,t} is a
+// 3-node hyperedge}, connected through pairs, and no larger hyperedge inside.
+// Nodes z outside e fall in classes by adjacency to (s, o): 1 = s only, 2 = o
+// only, 3 = both; A_1, A_2, A_3 partition A = N(s) u N(o) \ e.  All work is
+// done from s's side:
+//   first term without T: class sizes |A_3| = t_e, |A_1| = d_s - 1 - t_e,
+//     |A_2| = d_o - 1 - t_e; pairs of A joined by a pair, per class pair, from
+//     the triangles at s and o, and for each neighbour x of s the
+//     intersections of N(x) with N(s), N(o) and both; pairs of A not joined by
+//     complement; sets with y hanging off x alone from the neighbour-degree sums;
+//   pairs touching T are taken off through the rows of the nodes of T;
+//   second term: the 3-node hyperedges at s one by one, those at o from its
+//     8-bin pattern histogram (valid when neither other node meets s's side),
+//     corrected one by one for the 3-node hyperedges {o, y, z} where y or z is
+//     in N(s) u T or {s, y, z} is a 3-node hyperedge; the 4-node hyperedges
+//     holding e one by one.
+// One workgroup per sample.
+struct J2SparseLds {
+  unsigned long long acc[8];   // |A_3|, sums for A_3: codeg(s,x)-1, codeg(o,x)-1, |N(x) n A_3|, deg; for A_1: codeg(o,x)-1
+  unsigned long long adj_tt[16];   // joined pairs inside T by (class, class), from both ends
+  uint32_t tcls[4];
+  // flat walks over up to 256 items, each with up to three row segments
+  uint32_t pre[kThreads + 1];
+  uint32_t wave_tot[kWavesPerBlock];
+  uint32_t item[kThreads];
+  uint32_t seg_base[kThreads][3];
+  uint32_t seg_len[kThreads][3];
+  uint32_t cnt[kThreads][7];
+};
+
+// Walk, for items [0, n) 256 at a time, the concatenated segments seg(i)
+// defines (up to three, each a start and a length), as one flat range over
+// the workgroup: body(slot, segment, position) for every position; then
+// fin(slot, item) once per item.  Every thread must call it.
+template <typename Seg, typename Body, typename Fin>
+__device__ void block_flat(uint32_t n, J2SparseLds& L, Seg seg, Body body, Fin fin) {
+  const uint32_t tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
+  for (uint32_t c0 = 0; c0 < n; c0 += kThreads) {
+    uint32_t len = 0;
+    L.seg_len[tid][0] = L.seg_len[tid][1] = L.seg_len[tid][2] = 0;
+    for (int q = 0; q < 7; ++q) L.cnt[tid][q] = 0;
+    if (c0 + tid < n) {
+      seg(c0 + tid, L.seg_base[tid], L.seg_len[tid]);
+      len = L.seg_len[tid][0] + L.seg_len[tid][1] + L.seg_len[tid][2];
+    }
+    L.item[tid] = c0 + tid;
+    uint32_t wtot;
+    uint32_t off = wave_exclusive_scan(len, &wtot);
+    if (lane == 0) L.wave_tot[wv] = wtot;
+    __syncthreads();
+    for (uint32_t q = 0; q < wv; ++q) off += L.wave_tot[q];
+    L.pre[tid] = off;
+    if (tid == kThreads - 1) L.pre[kThreads] = off + len;
+    __syncthreads();
+    const uint32_t work = L.pre[kThreads];
+    for (uint32_t t = tid; t < work; t += kThreads) {
+      uint32_t lo = 0, hi = kThreads;   // pre[lo] <= t < pre[hi]
+      while (hi - lo > 1) {
+        const uint32_t m = (lo + hi) >> 1;
+        if (L.pre[m] <= t) lo = m; else hi = m;
+      }
+      uint32_t k = t - L.pre[lo], sg = 0;
+      while (k >= L.seg_len[lo][sg]) {
+        k -= L.seg_len[lo][sg];
+        ++sg;
+      }
+      body(lo, sg, L.seg_base[lo][sg] + k);
+    }
+    __syncthreads();
+    if (c0 + tid < n) fin(tid, c0 + tid);
+    __syncthreads();
   }
-  if (set128_has(v.hs4, key4(q[0], q[1], q[2], q[3]))) return;
-  // local positions u=0, w=1, x=2, y=3
-  const uint32_t p = 1u | (has2(v.hs2, u, x) << 1) | (has2(v.hs2, w, x) << 2) | (has2(v.hs2, u, y) << 4) |
-                     (has2(v.hs2, w, y) << 5) | (has2(v.hs2, x, y) << 7);
-  const uint8_t cls = lut[p];
-  if (cls != 0xFF) atomicAdd(&h[cls], 1ull);
 }
 
-__device__ void sample_j2_k4_hash(const View& v, const Draws& d, uint32_t part, uint32_t n_parts,
-                                  const uint8_t* lut, unsigned long long* h_lds, unsigned long long* rows) {
-  for (uint64_t s = part; s < d.S[2]; s += n_parts) {
-    const uint64_t i = d.at(2, s);
+__device__ inline uint32_t j2_pat(uint32_t cx, uint32_t cy, uint32_t xy) {
+  return 1u | ((cx & 1u) << 1) | ((cx >> 1) << 2) | ((cy & 1u) << 4) | ((cy >> 1) << 5) | (xy << 7);
+}
+
+__device__ void sample_j2_k4_sparse(const View& v, const PairLinks& pl, const NodeStats& ns,
+                                    const unsigned long long* __restrict__ es, const Draws& d,
+                                    uint32_t part, uint32_t n_parts, J2SparseLds& L, const uint8_t* lut,
+                                    unsigned long long* h_lds, unsigned long long* rows) {
+  const uint32_t tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
+  for (uint64_t smp = part; smp < d.S[2]; smp += n_parts) {
+    const uint64_t i = d.at(2, smp);
     if (i >= d.n[2]) continue;
-    unsigned long long* h = row_or(rows, s, h_lds);
-    const uint32_t u = v.e2[2 * i], w = v.e2[2 * i + 1];
-    const uint32_t ub = v.g2_off[u], du = v.g2_off[u + 1] - ub;
-    const uint32_t wb = v.g2_off[w], dw = v.g2_off[w + 1] - wb;
-    const uint64_t nL = uint64_t(du) + dw;
-    auto valid = [&](uint32_t p, uint32_t x) { return x != u && x != w && (p < du || !has2(v.hs2, u, x)); };
-    // both other nodes adjacent to e
-    const uint64_t npairs = nL * (nL - 1) / 2;
-    for (uint64_t t = threadIdx.x; t < npairs; t += kThreads) {
-      uint32_t p, q;
-      pair_from_index(t, nL, p, q);
-      const uint32_t x = nodeL(v.g2_adj, ub, du, wb, p), y = nodeL(v.g2_adj, ub, du, wb, q);
-      if (!valid(p, x) || !valid(q, y)) continue;
-      j2_candidate(v, u, w, x, y, lut, h);
+    unsigned long long* h = row_or(rows, smp, h_lds);
+    const uint32_t e0 = v.e2[2 * i], e1 = v.e2[2 * i + 1];
+    const uint32_t d0 = deg2_of(v, e0), d1 = deg2_of(v, e1);
+    const uint32_t s = d0 <= d1 ? e0 : e1, o = d0 <= d1 ? e1 : e0;
+    const uint32_t ds = d0 <= d1 ? d0 : d1, dO = d0 <= d1 ? d1 : d0;
+    const unsigned long long key = ((unsigned long long)e0 << 32) | e1;
+    const uint64_t tlo = pl.n ? pl_lower(pl, key) : 0, thi = pl.n ? pl_lower(pl, key + 1) : 0;
+    const bool any_t = thi > tlo;
+    auto in_t = [&](uint32_t y) { return any_t && has3(v.hs3, s, o, y); };
+    auto in_x = [&](uint32_t y) { return y == s || y == o || in_t(y); };
+    auto cls_of = [&](uint32_t y) { return has2(v.hs2, s, y) | (has2(v.hs2, o, y) << 1); };
+    auto t_node = [&](uint64_t p) {
+      const uint32_t* f = v.e3 + 3ull * pl.edge[p];
+      return f[0] ^ f[1] ^ f[2] ^ s ^ o;
+    };
+    auto sub = [&](uint32_t pat, unsigned long long n) {
+      const uint8_t c = lut[pat];
+      if (c != 0xFF && n) atomicAdd(&h[c], 0ull - n);
+    };
+    auto add = [&](uint32_t pat, unsigned long long n) {
+      const uint8_t c = lut[pat];
+      if (c != 0xFF && n) atomicAdd(&h[c], n);
+    };
+    if (tid < 8) L.acc[tid] = 0;
+    if (tid < 16) L.adj_tt[tid] = 0;
+    if (tid < 4) L.tcls[tid] = 0;
+    __syncthreads();
+    // ---- the neighbourhood sums of e, from the per-pair statistics: with C
+    // the common neighbours, |C| = t_e; over x in C: codeg(s,x)-1, codeg(o,x)-1,
+    // |N(x) n C| (twice the 4-cliques through e) and deg x; over the other
+    // neighbours x of s: codeg(o,x)-1 = (4-cycles through e) - sum over C of (codeg(o,x)-1)
+    if (tid == 0) {
+      const uint64_t n2 = d.n[2];
+      const unsigned long long te = es[i], k4 = es[n2 + i], c4 = es[2 * n2 + i];
+      const unsigned long long s_lo = es[3 * n2 + i], s_hi = es[4 * n2 + i], dsum = es[5 * n2 + i];
+      const unsigned long long ss = s == e0 ? s_lo : s_hi, so = s == e0 ? s_hi : s_lo;
+      L.acc[0] = te;
+      L.acc[1] = ss - te;
+      L.acc[2] = so - te;
+      L.acc[3] = 2 * k4;
+      L.acc[4] = dsum;
+      L.acc[5] = c4 - (so - te);
     }
-    // x adjacent to e, y adjacent to x only
-    for (uint32_t p = 0; p < nL; ++p) {
-      const uint32_t x = nodeL(v.g2_adj, ub, du, wb, p);
-      if (!valid(p, x)) continue;
-      const uint32_t xb = v.g2_off[x], xe = v.g2_off[x + 1];
-      for (uint32_t yi = xb + threadIdx.x; yi < xe; yi += kThreads) {
-        const uint32_t y = v.g2_adj[yi];
-        if (y == u || y == w || has2(v.hs2, u, y) || has2(v.hs2, w, y)) continue;
-        j2_candidate(v, u, w, x, y, lut, h);
+    // class sizes of T
+    for (uint64_t p = tlo + tid; p < thi; p += kThreads) atomicAdd(&L.tcls[cls_of(t_node(p))], 1u);
+    __syncthreads();
+    const unsigned long long n3 = L.acc[0];
+    const unsigned long long na[4] = {0, ds - 1 - n3, dO - 1 - n3, n3};
+    // ---- pairs touching T.  The neighbours y of t outside e, by class,
+    // follow from |N(t) n N(s)|, |N(t) n N(s) n N(o)| (the shorter of the two
+    // rows walked) and |N(t) n N(o)| (likewise); those inside T from the
+    // shorter of N(t) and T.  Pairs with both nodes in T are taken off once,
+    // by class, at the end.
+    const uint32_t n_t = uint32_t(thi - tlo);
+    block_flat(
+        n_t, L,
+        [&](uint32_t j, uint32_t* base, uint32_t* len) {
+          const uint32_t t = t_node(tlo + j);
+          const uint32_t dt = deg2_of(v, t);
+          base[0] = dt <= ds ? v.g2_off[t] : v.g2_off[s];
+          len[0] = dt <= ds ? dt : ds;
+          base[1] = dt <= dO ? v.g2_off[t] : v.g2_off[o];
+          len[1] = dt <= dO ? dt : dO;
+          base[2] = dt <= n_t ? v.g2_off[t] : uint32_t(tlo);
+          len[2] = dt <= n_t ? dt : n_t;
+        },
+        [&](uint32_t slot, uint32_t sg, uint32_t pos) {
+          const uint32_t t = t_node(tlo + L.item[slot]);
+          const uint32_t dt = deg2_of(v, t);
+          if (sg == 0) {
+            const uint32_t z = v.g2_adj[pos];
+            const uint32_t hit = dt <= ds ? has2(v.hs2, s, z) : has2(v.hs2, t, z);
+            if (hit) {
+              atomicAdd(&L.cnt[slot][0], 1u);
+              if (has2(v.hs2, o, z)) atomicAdd(&L.cnt[slot][1], 1u);
+            }
+          } else if (sg == 1) {
+            const uint32_t z = v.g2_adj[pos];
+            if (dt <= dO ? has2(v.hs2, o, z) : has2(v.hs2, t, z)) atomicAdd(&L.cnt[slot][2], 1u);
+          } else {
+            uint32_t y;
+            if (dt <= n_t) {
+              y = v.g2_adj[pos];
+              if (y == s || y == o || !in_t(y)) return;
+            } else {
+              y = t_node(pos);
+              if (y == t || !has2(v.hs2, t, y)) return;
+            }
+            atomicAdd(&L.cnt[slot][3 + cls_of(y)], 1u);
+          }
+        },
+        [&](uint32_t slot, uint32_t j) {
+          const uint32_t t = t_node(tlo + j);
+          const uint32_t ts = has2(v.hs2, s, t), to = has2(v.hs2, o, t);
+          const uint32_t ct = ts | (to << 1);
+          const uint32_t dt = deg2_of(v, t);
+          const uint32_t a_s = L.cnt[slot][0], a_so = L.cnt[slot][1], a_o = L.cnt[slot][2];
+          const uint32_t q0 = L.cnt[slot][3], q1 = L.cnt[slot][4], q2 = L.cnt[slot][5], q3 = L.cnt[slot][6];
+          const uint32_t c3 = a_so, c1 = a_s - to - a_so, c2 = a_o - ts - a_so;
+          const uint32_t c0 = dt - ts - to - c1 - c2 - c3;
+          // neighbours outside T by class
+          const unsigned long long m0 = c0 - q0, m1 = c1 - q1, m2 = c2 - q2, m3 = c3 - q3;
+          if (ct) {
+            sub(j2_pat(ct, 1, 1), m1);
+            sub(j2_pat(ct, 2, 1), m2);
+            sub(j2_pat(ct, 3, 1), m3);
+            sub(j2_pat(ct, 0, 1), m0);
+            // pairs {t, y}, y in A outside T, not joined
+            sub(j2_pat(ct, 1, 0), na[1] - L.tcls[1] - m1);
+            sub(j2_pat(ct, 2, 0), na[2] - L.tcls[2] - m2);
+            sub(j2_pat(ct, 3, 0), na[3] - L.tcls[3] - m3);
+          } else {
+            sub(j2_pat(1, 0, 1), m1);
+            sub(j2_pat(2, 0, 1), m2);
+            sub(j2_pat(3, 0, 1), m3);
+          }
+          // joined pairs inside T, each seen from both ends
+          if (q0) atomicAdd(&L.adj_tt[ct * 4 + 0], (unsigned long long)q0);
+          if (q1) atomicAdd(&L.adj_tt[ct * 4 + 1], (unsigned long long)q1);
+          if (q2) atomicAdd(&L.adj_tt[ct * 4 + 2], (unsigned long long)q2);
+          if (q3) atomicAdd(&L.adj_tt[ct * 4 + 3], (unsigned long long)q3);
+        });
+    // ---- second term
+    auto remove = [&](uint32_t x, uint32_t y) {
+      if (in_x(x) || in_x(y)) return;
+      sub(1u | (has2(v.hs2, s, x) << 1) | (has2(v.hs2, o, x) << 2) | (has2(v.hs2, s, y) << 4) |
+              (has2(v.hs2, o, y) << 5) | (has2(v.hs2, x, y) << 7),
+          1);
+    };
+    // a 3-node hyperedge {o, y, z} as the histogram at o counts it
+    auto agg_pat = [&](uint32_t y, uint32_t z) {
+      if (z < y) {
+        const uint32_t t = y;
+        y = z;
+        z = t;
+      }
+      return 1u | (has2(v.hs2, o, y) << 2) | (has2(v.hs2, o, z) << 5) | (has2(v.hs2, y, z) << 7);
+    };
+    auto near_s = [&](uint32_t y) { return has2(v.hs2, s, y) || in_t(y); };
+    // at s, one by one (and the hyperedges at o that match one at s on the far side)
+    for (uint32_t p = v.i3_off[s] + tid; p < v.i3_off[s + 1]; p += kThreads) {
+      const uint32_t* f = v.e3 + 3ull * v.i3_idx[p];
+      if (f[0] == o || f[1] == o || f[2] == o) continue;
+      const uint32_t y = f[0] == s ? f[1] : f[0], z = f[2] == s ? f[1] : f[2];
+      remove(y, z);
+      if (!near_s(y) && !near_s(z) && has3(v.hs3, o, y, z)) add(agg_pat(y, z), 1);
+    }
+    // at o, from its histogram
+    if (tid < 8) {
+      const uint32_t b = tid;
+      sub(1u | ((b & 1u) << 2) | (((b >> 1) & 1u) << 5) | ((b >> 2) << 7), ns.h3[8ull * o + b]);
+    }
+    // corrections: the hyperedges {s, o, t}
+    for (uint64_t p = tlo + tid; p < thi; p += kThreads) add(agg_pat(s, t_node(p)), 1);
+    // corrections: {o, y, z} with y in N(s) u T (taken from the smaller of y, z when both are)
+    {
+      const uint32_t sb = v.g2_off[s];
+      auto y_of = [&](uint32_t j) { return j < ds ? v.g2_adj[sb + j] : t_node(tlo + (j - ds)); };
+      block_flat(
+          ds + n_t, L,
+          [&](uint32_t j, uint32_t* base, uint32_t* len) {
+            const uint32_t y = y_of(j);
+            if (y == o || (j >= ds && has2(v.hs2, s, y))) return;   // o, or a node of T taken as a neighbour of s
+            const unsigned long long ky =
+                y < o ? (((unsigned long long)y << 32) | o) : (((unsigned long long)o << 32) | y);
+            const uint64_t lo = pl_lower(pl, ky);
+            base[0] = uint32_t(lo);
+            len[0] = uint32_t(pl_lower(pl, ky + 1) - lo);
+          },
+          [&](uint32_t slot, uint32_t, uint32_t r) {
+            const uint32_t y = y_of(L.item[slot]);
+            const uint32_t* f = v.e3 + 3ull * pl.edge[r];
+            const uint32_t z = f[0] ^ f[1] ^ f[2] ^ o ^ y;
+            if (z == s) return;                 // an {s, o, t}
+            if (z < y && near_s(z)) return;     // taken from z
+            add(agg_pat(y, z), 1);
+            if (has3(v.hs3, s, y, z)) return;   // removed at s
+            remove(y, z);
+          },
+          [](uint32_t, uint32_t) {});
+    }
+    // 4-node hyperedges holding e
+    {
+      const uint32_t fs = v.i4_off[s + 1] - v.i4_off[s], fo = v.i4_off[o + 1] - v.i4_off[o];
+      const uint32_t a = fs <= fo ? s : o, other = fs <= fo ? o : s;
+      for (uint32_t p = v.i4_off[a] + tid; p < v.i4_off[a + 1]; p += kThreads) {
+        const uint32_t* f = v.e4 + 4ull * v.i4_idx[p];
+        const uint32_t g0 = f[0], g1 = f[1], g2 = f[2], g3 = f[3];
+        if (g0 != other && g1 != other && g2 != other && g3 != other) continue;
+        uint32_t x = 0xFFFFFFFFu, y = 0xFFFFFFFFu;
+        for (const uint32_t m : {g0, g1, g2, g3}) {
+          if (m == s || m == o) continue;
+          if (x == 0xFFFFFFFFu) x = m; else y = m;
+        }
+        if (has3(v.hs3, s, x, y) || has3(v.hs3, o, x, y)) continue;   // removed with a 3-node hyperedge
+        remove(x, y);
       }
     }
+    __syncthreads();
+    // ---- first term (all of A), and the pairs inside T not joined
+    if (tid == 0) {
+      const unsigned long long cs = L.acc[1], co = L.acc[2], cc = L.acc[3], d3 = L.acc[4], c1o = L.acc[5];
+      const unsigned long long e33 = cc / 2, e13 = cs - cc, e23 = co - cc;
+      const unsigned long long e11 = (ns.tri[s] - n3) - e13 - e33;
+      const unsigned long long e22 = (ns.tri[o] - n3) - e23 - e33;
+      const unsigned long long e12 = c1o - e13;
+      const unsigned long long dsum[4] = {0, ns.nbr[s] - dO - d3, ns.nbr[o] - ds - d3, d3};
+      const unsigned long long e[4][4] = {{0, 0, 0, 0}, {0, e11, e12, e13}, {0, e12, e22, e23}, {0, e13, e23, e33}};
+      for (uint32_t p = 1; p <= 3; ++p) {
+        for (uint32_t q = p; q <= 3; ++q) {
+          const unsigned long long tot = p == q ? na[p] * (na[p] - (na[p] > 0)) / 2 : na[p] * na[q];
+          add(j2_pat(p, q, 1), e[p][q]);
+          add(j2_pat(p, q, 0), tot - e[p][q]);
+          // pairs inside T in these classes: joined (seen twice) and not joined
+          const unsigned long long tp = L.tcls[p], tq = L.tcls[q];
+          const unsigned long long ttot = p == q ? tp * (tp - (tp > 0)) / 2 : tp * tq;
+          const unsigned long long tadj = p == q ? L.adj_tt[p * 4 + p] / 2 : L.adj_tt[p * 4 + q];
+          sub(j2_pat(p, q, 1), tadj);
+          sub(j2_pat(p, q, 0), ttot - tadj);
+        }
+        // joined pairs inside T with one node outside A: it hangs off the other
+        sub(j2_pat(p, 0, 1), L.adj_tt[p * 4 + 0]);
+        const unsigned long long inside = 2 * e[p][p] + e[p][1] + e[p][2] + e[p][3] - e[p][p];
+        add(j2_pat(p, 0, 1), dsum[p] - na[p] * (p == 3 ? 2 : 1) - inside);
+      }
+    }
+    __syncthreads();
   }
 }
 
@@ -381,6 +633,9 @@ struct ScaleArgs {
 
 struct SampledArgs {
   View v;
+  PairLinks pl;                  // pair -> 3-node hyperedge index (no bit rows)
+  NodeStats ns;                  // per-node statistics (no bit rows)
+  const unsigned long long* es;  // per-pair statistics (no bit rows)
   Draws d;
   const uint8_t* lut;
   uint32_t blocks[5];            // workgroups of strata 2, 3, 4 (in this order in the grid)
@@ -405,7 +660,7 @@ struct SampledLds<4, true> {
 };
 template <>
 struct SampledLds<4, false> {
-  uint32_t unused;
+  J2SparseLds j2;
 };
 
 // Every stratum's samples in one launch.  The grid holds a.blocks[2]
@@ -429,14 +684,14 @@ __global__ void __launch_bounds__(kThreads) k_sampled(SampledArgs a, ScaleArgs s
     if constexpr (K == 4 && BITS)
       sample_j2_k4_bits(a.v, a.d, b, a.blocks[2], lds.j2, lut, h_lds, a.rows[2]);
     else if constexpr (K == 4)
-      sample_j2_k4_hash(a.v, a.d, b, a.blocks[2], lut, h_lds, a.rows[2]);
+      sample_j2_k4_sparse(a.v, a.pl, a.ns, a.es, a.d, b, a.blocks[2], lds.j2, lut, h_lds, a.rows[2]);
     else
       sample_j2_k3(a.v, a.d, b, a.blocks[2], lut, h_lds, a.rows[2]);
   } else if ((b -= a.blocks[2]) < a.blocks[3]) {
     if constexpr (K == 4 && BITS)
-      sample_j3_k4<true>(a.v, a.d, b, a.blocks[3], lds.b4, lut, h_lds, a.rows[3]);
+      sample_j3_k4<true>(a.v, a.pl, a.d, b, a.blocks[3], lds.b4, lut, h_lds, a.rows[3]);
     else if constexpr (K == 4)
-      sample_j3_k4<false>(a.v, a.d, b, a.blocks[3], nullptr, lut, h_lds, a.rows[3]);
+      sample_j3_k4<false>(a.v, a.pl, a.d, b, a.blocks[3], nullptr, lut, h_lds, a.rows[3]);
     else
       sample_j3_k3(a.v, a.d, b, a.blocks[3], lut, h_lds, a.rows[3]);
   } else if (K == 4) {
@@ -490,8 +745,20 @@ int launch_sampled(const hm_graph* H, int k, const uint32_t* const idx[5], const
     set_error("bit rows of %u words exceed the sampler's %u", H->words, kMaxWordsJ2);
     return HM_EINTERNAL;
   }
+  if (k == 4 && !bits) {
+    HM_TRY(ensure_pair_links(const_cast<hm_graph*>(H), st));
+    HM_TRY(ensure_node_stats(const_cast<hm_graph*>(H), st));
+    HM_TRY(ensure_edge_stats(const_cast<hm_graph*>(H), st));
+  }
   SampledArgs a;
   a.v = view_of(H);
+  a.pl.keys = H->pl_keys;
+  a.pl.edge = H->pl_edge;
+  a.pl.n = H->pl_keys ? 3 * H->n_by_size[3] : 0;
+  a.ns.tri = H->ns_tri;
+  a.ns.nbr = H->ns_nbr;
+  a.ns.h3 = H->ns_h3;
+  a.es = H->es;
   for (int j = 0; j < 5; ++j) {
     const bool in = j >= 2 && j <= k;
     a.d.idx[j] = in ? idx[j] : nullptr;

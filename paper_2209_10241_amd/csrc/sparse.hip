@@ -100,9 +100,12 @@ __global__ void __launch_bounds__(kThreads) k_sp_nodes(View v, const unsigned lo
 // rows of those that precede u are walked as one flat range.  cnt and the
 // list of touched w are private to the workgroup (N entries each, zero
 // between nodes).
+template <bool PER_EDGE>
 __global__ void __launch_bounds__(kThreads) k_sp_c4(View v, uint32_t* __restrict__ cnt_all,
                                                     uint32_t* __restrict__ touched_all,
-                                                    unsigned long long* __restrict__ acc) {
+                                                    unsigned long long* __restrict__ acc,
+                                                    const uint32_t* __restrict__ eid,
+                                                    unsigned long long* __restrict__ c4e) {
   __shared__ uint32_t pre[kThreads + 1];
   __shared__ uint32_t vv[kThreads];
   __shared__ uint32_t wave_tot[kWavesPerBlock];
@@ -115,34 +118,47 @@ __global__ void __launch_bounds__(kThreads) k_sp_c4(View v, uint32_t* __restrict
     const uint32_t ub = v.g2_off[u], ue = v.g2_off[u + 1];
     if (ue - ub < 2) continue;
     if (tid == 0) n_touched = 0;
-    for (uint32_t c0 = ub; c0 < ue; c0 += kThreads) {
-      uint32_t x = 0, len = 0;
-      if (c0 + tid < ue) {
-        x = v.g2_adj[c0 + tid];
-        if (rank_less(v, x, u)) len = deg2_of(v, x);
-      }
-      uint32_t wtot;
-      uint32_t off = wave_exclusive_scan(len, &wtot);
-      if (lane == 0) wave_tot[wv] = wtot;
-      __syncthreads();
-      for (uint32_t q = 0; q < wv; ++q) off += wave_tot[q];
-      vv[tid] = x;
-      pre[tid] = off;
-      if (tid == kThreads - 1) pre[kThreads] = off + len;
-      __syncthreads();
-      const uint32_t work = pre[kThreads];
-      for (uint32_t t = tid; t < work; t += kThreads) {
-        uint32_t lo = 0, hi = kThreads;   // pre[lo] <= t < pre[hi]
-        while (hi - lo > 1) {
-          const uint32_t m = (lo + hi) >> 1;
-          if (pre[m] <= t) lo = m; else hi = m;
+    // pass 0 counts the middle nodes per opposite node; with PER_EDGE, pass 1
+    // gives each wedge (u, x, w) the cnt[w] - 1 cycles it closes, on its two pairs
+    for (int pass = 0; pass < (PER_EDGE ? 2 : 1); ++pass) {
+      for (uint32_t c0 = ub; c0 < ue; c0 += kThreads) {
+        uint32_t x = 0, len = 0;
+        if (c0 + tid < ue) {
+          x = v.g2_adj[c0 + tid];
+          if (rank_less(v, x, u)) len = deg2_of(v, x);
         }
-        const uint32_t y = vv[lo];
-        const uint32_t w = v.g2_adj[v.g2_off[y] + (t - pre[lo])];
-        if (w == u || !rank_less(v, w, u)) continue;
-        if (atomicAdd(&cnt[w], 1u) == 0u) touched[atomicAdd(&n_touched, 1u)] = w;
+        uint32_t wtot;
+        uint32_t off = wave_exclusive_scan(len, &wtot);
+        if (lane == 0) wave_tot[wv] = wtot;
+        __syncthreads();
+        for (uint32_t q = 0; q < wv; ++q) off += wave_tot[q];
+        vv[tid] = x;
+        pre[tid] = off;
+        if (tid == kThreads - 1) pre[kThreads] = off + len;
+        __syncthreads();
+        const uint32_t work = pre[kThreads];
+        for (uint32_t t = tid; t < work; t += kThreads) {
+          uint32_t lo = 0, hi = kThreads;   // pre[lo] <= t < pre[hi]
+          while (hi - lo > 1) {
+            const uint32_t m = (lo + hi) >> 1;
+            if (pre[m] <= t) lo = m; else hi = m;
+          }
+          const uint32_t y = vv[lo];
+          const uint32_t pw = v.g2_off[y] + (t - pre[lo]);
+          const uint32_t w = v.g2_adj[pw];
+          if (w == u || !rank_less(v, w, u)) continue;
+          if (pass == 0) {
+            if (atomicAdd(&cnt[w], 1u) == 0u) touched[atomicAdd(&n_touched, 1u)] = w;
+          } else {
+            const uint32_t c = __hip_atomic_load(&cnt[w], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) - 1u;
+            if (c) {
+              atomicAdd(&c4e[eid[c0 + lo]], (unsigned long long)c);
+              atomicAdd(&c4e[eid[pw]], (unsigned long long)c);
+            }
+          }
+        }
+        __syncthreads();
       }
-      __syncthreads();
     }
     const uint32_t nt = n_touched;
     for (uint32_t i = tid; i < nt; i += kThreads) {
@@ -167,12 +183,25 @@ __global__ void k_sp_outdeg(View v, uint32_t* __restrict__ outdeg) {
 // W = common neighbours after hi; every pair of W joined by a pair of G2
 // closes one 4-clique, found once at its first two nodes.  One wavefront per
 // pair; W goes to a per-wavefront list of cap entries.
+__device__ inline uint32_t row_pos(const View& v, uint32_t r, uint32_t x) {
+  uint32_t lo = v.g2_off[r], hi = v.g2_off[r + 1];
+  while (lo < hi) {
+    const uint32_t m = lo + ((hi - lo) >> 1);
+    if (v.g2_adj[m] < x) lo = m + 1; else hi = m;
+  }
+  return lo;
+}
+
+template <bool PER_EDGE>
 __global__ void __launch_bounds__(kThreads) k_sp_k4(View v, uint64_t n2, uint32_t cap, uint32_t* __restrict__ wlist,
-                                                    unsigned long long* __restrict__ acc) {
+                                                    unsigned long long* __restrict__ acc,
+                                                    const uint32_t* __restrict__ eid,
+                                                    unsigned long long* __restrict__ k4e) {
   const uint32_t lane = threadIdx.x & (kWave - 1);
   const uint64_t wave = uint64_t(blockIdx.x) * kWavesPerBlock + threadIdx.x / kWave;
   const uint64_t n_waves = uint64_t(gridDim.x) * kWavesPerBlock;
-  uint32_t* W = wlist + wave * cap;
+  uint32_t* W = wlist + wave * cap * (PER_EDGE ? 2 : 1);
+  uint32_t* Wp = W + cap;   // position of each W entry in lo's row (PER_EDGE)
   unsigned long long total = 0;
   for (uint64_t e = wave; e < n2; e += n_waves) {
     uint32_t lo = v.e2[2 * e], hi = v.e2[2 * e + 1];
@@ -191,19 +220,75 @@ __global__ void __launch_bounds__(kThreads) k_sp_k4(View v, uint64_t n2, uint32_
         keep = rank_less(v, hi, w) && has2(v.hs2, hi, w);
       }
       const unsigned long long m = __ballot(keep);
-      if (keep) W[nw + __popcll(m & ((1ull << lane) - 1ull))] = w;
+      if (keep) {
+        const uint32_t slot = nw + uint32_t(__popcll(m & ((1ull << lane) - 1ull)));
+        W[slot] = w;
+        if (PER_EDGE) Wp[slot] = p;
+      }
       nw += uint32_t(__popcll(m));
     }
     wave_sync();
     uint32_t c = 0;
     for (uint32_t i = 0; i + 1 < nw; ++i) {
       const uint32_t wi = W[i];
-      for (uint32_t j = i + 1 + lane; j < nw; j += kWave) c += has2(v.hs2, wi, W[j]);
+      for (uint32_t j = i + 1 + lane; j < nw; j += kWave) {
+        const uint32_t wj = W[j];
+        if (!has2(v.hs2, wi, wj)) continue;
+        ++c;
+        if (PER_EDGE) {
+          // the six pairs of {lo, hi, wi, wj}
+          atomicAdd(&k4e[e], 1ull);
+          atomicAdd(&k4e[eid[Wp[i]]], 1ull);
+          atomicAdd(&k4e[eid[Wp[j]]], 1ull);
+          atomicAdd(&k4e[eid[row_pos(v, hi, wi)]], 1ull);
+          atomicAdd(&k4e[eid[row_pos(v, hi, wj)]], 1ull);
+          const bool ci = deg2_of(v, wi) <= deg2_of(v, wj);
+          atomicAdd(&k4e[eid[ci ? row_pos(v, wi, wj) : row_pos(v, wj, wi)]], 1ull);
+        }
+      }
     }
     total += wave_sum_u32(c);
     wave_sync();
   }
   if (lane == 0) atomicAdd(acc + kAccK4, total);
+}
+
+// Per pair e = {u < w}: over the common neighbours x, the sums of t_{ux},
+// t_{wx} and deg x (the smaller row walked, the other row searched).
+__global__ void __launch_bounds__(kThreads) k_es_sums(View v, uint64_t n2, const uint32_t* __restrict__ eid,
+                                                      const uint32_t* __restrict__ tri_e,
+                                                      unsigned long long* __restrict__ su,
+                                                      unsigned long long* __restrict__ sw,
+                                                      unsigned long long* __restrict__ sd) {
+  const uint32_t lane = threadIdx.x & (kWave - 1);
+  const uint64_t wave = uint64_t(blockIdx.x) * kWavesPerBlock + threadIdx.x / kWave;
+  const uint64_t n_waves = uint64_t(gridDim.x) * kWavesPerBlock;
+  for (uint64_t e = wave; e < n2; e += n_waves) {
+    const uint32_t u = v.e2[2 * e], w = v.e2[2 * e + 1];
+    const bool walk_u = deg2_of(v, u) <= deg2_of(v, w);
+    const uint32_t r = walk_u ? u : w, o = walk_u ? w : u;
+    unsigned long long a = 0, b = 0, c = 0;   // sums over the walked and the searched side
+    for (uint32_t p = v.g2_off[r] + lane; p < v.g2_off[r + 1]; p += kWave) {
+      const uint32_t x = v.g2_adj[p];
+      if (!has2(v.hs2, o, x)) continue;
+      a += tri_e[eid[p]];
+      b += tri_e[eid[row_pos(v, o, x)]];
+      c += deg2_of(v, x);
+    }
+    a = wave_sum(a);
+    b = wave_sum(b);
+    c = wave_sum(c);
+    if (lane == 0) {
+      su[e] = walk_u ? a : b;
+      sw[e] = walk_u ? b : a;
+      sd[e] = c;
+    }
+  }
+}
+
+__global__ void k_es_widen(const uint32_t* __restrict__ t32, uint64_t n, unsigned long long* __restrict__ t64) {
+  for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += uint64_t(gridDim.x) * blockDim.x)
+    t64[i] = t32[i];
 }
 
 // (b) at order 4 without bit rows: one wavefront per 3-node hyperedge.
@@ -285,6 +370,136 @@ unsigned grid_cap(uint64_t items, uint64_t per_block, unsigned cap) {
 }
 
 }  // namespace
+
+namespace {
+
+__global__ void k_ns_half(const unsigned long long* __restrict__ tv, uint32_t n, unsigned long long* __restrict__ tri) {
+  for (uint32_t x = blockIdx.x * blockDim.x + threadIdx.x; x < n; x += gridDim.x * blockDim.x) tri[x] = tv[x] / 2;
+}
+
+// sum of the neighbours' degrees, per node
+__global__ void k_ns_nbr(View v, uint64_t n2, unsigned long long* __restrict__ nbr) {
+  for (uint64_t e = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < n2; e += uint64_t(gridDim.x) * blockDim.x) {
+    const uint32_t a = v.e2[2 * e], b = v.e2[2 * e + 1];
+    atomicAdd(&nbr[a], (unsigned long long)deg2_of(v, b));
+    atomicAdd(&nbr[b], (unsigned long long)deg2_of(v, a));
+  }
+}
+
+// per node o, its 3-node hyperedges {o, y, z} (y < z) by (o~y, o~z, y~z)
+__global__ void k_ns_h3(View v, uint64_t n3, uint32_t* __restrict__ h3) {
+  for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n3; i += uint64_t(gridDim.x) * blockDim.x) {
+    const uint32_t a = v.e3[3 * i], b = v.e3[3 * i + 1], c = v.e3[3 * i + 2];
+    const uint32_t pab = has2(v.hs2, a, b), pac = has2(v.hs2, a, c), pbc = has2(v.hs2, b, c);
+    atomicAdd(&h3[8ull * a + (pab | (pac << 1) | (pbc << 2))], 1u);
+    atomicAdd(&h3[8ull * b + (pab | (pbc << 1) | (pac << 2))], 1u);
+    atomicAdd(&h3[8ull * c + (pac | (pbc << 1) | (pab << 2))], 1u);
+  }
+}
+
+}  // namespace
+
+// Per-node statistics of H for the pair samplers without bit rows, built on
+// first use: triangles at each node, the sum of its neighbours' degrees, and
+// its 3-node hyperedges by pairwise pattern.
+int ensure_node_stats(hm_graph* H, hipStream_t st) {
+  if (H->ns_tri) return HM_OK;
+  const View v = view_of(H);
+  const uint64_t n2 = H->n_by_size[2], n3 = H->n_by_size[3], N = H->n_nodes;
+  Scratch tmp;
+  unsigned long long *acc = nullptr, *tv = nullptr;
+  uint32_t* tri_e = nullptr;
+  HM_TRY(tmp.get(&acc, kAccN));
+  HM_TRY(tmp.get(&tv, N));
+  HM_TRY(tmp.get(&tri_e, n2));
+  HM_TRY(fill_u64(acc, 0, kAccN, st));
+  HM_TRY(fill_u64(tv, 0, N, st));
+  void *p_tri = nullptr, *p_nbr = nullptr, *p_h3 = nullptr;
+  int rc = dalloc(&p_tri, N * sizeof(unsigned long long));
+  if (rc == HM_OK) rc = dalloc(&p_nbr, N * sizeof(unsigned long long));
+  if (rc == HM_OK) rc = dalloc(&p_h3, 8 * N * sizeof(uint32_t));
+  auto* tri = static_cast<unsigned long long*>(p_tri);
+  auto* nbr = static_cast<unsigned long long*>(p_nbr);
+  auto* h3 = static_cast<uint32_t*>(p_h3);
+  if (rc == HM_OK) rc = fill_u64(nbr, 0, N, st);
+  if (rc == HM_OK) rc = fill_u32(h3, 0, 8 * N, st);
+  if (rc == HM_OK) {
+    if (n2) k_sp_edge_tri<<<grid_cap(n2, kWavesPerBlock, 2048), kThreads, 0, st>>>(v, n2, tri_e, tv, acc);
+    k_ns_half<<<grid_cap(N, 256, 1024), 256, 0, st>>>(tv, uint32_t(N), tri);
+    if (n2) k_ns_nbr<<<grid_cap(n2, 256, 2048), 256, 0, st>>>(v, n2, nbr);
+    if (n3) k_ns_h3<<<grid_cap(n3, 256, 2048), 256, 0, st>>>(v, n3, h3);
+    if (hipGetLastError() != hipSuccess) rc = HM_EDEVICE;
+  }
+  if (rc == HM_OK && hipStreamSynchronize(st) != hipSuccess) rc = HM_EDEVICE;
+  if (rc != HM_OK) {
+    dfree(p_tri);
+    dfree(p_nbr);
+    dfree(p_h3);
+    return rc;
+  }
+  H->ns_tri = tri;
+  H->ns_nbr = nbr;
+  H->ns_h3 = h3;
+  return HM_OK;
+}
+
+// Per-pair statistics of H for the pair sampler without bit rows (layout in
+// hm_graph::es), built on first use.
+int ensure_edge_stats(hm_graph* H, hipStream_t st) {
+  if (H->es) return HM_OK;
+  const View v = view_of(H);
+  const uint64_t n2 = H->n_by_size[2], N = H->n_nodes;
+  void* p_es = nullptr;
+  HM_TRY(dalloc(&p_es, 6 * std::max<uint64_t>(n2, 1) * sizeof(unsigned long long)));
+  auto* es = static_cast<unsigned long long*>(p_es);
+  int rc = fill_u64(es, 0, 6 * n2, st);
+  {
+    Scratch tmp;
+    unsigned long long *acc = nullptr, *tv = nullptr;
+    uint32_t *tri_e = nullptr, *cnt = nullptr, *touched = nullptr, *outdeg = nullptr, *dmax = nullptr,
+             *wlist = nullptr;
+    const unsigned g = grid_cap(N, 1, unsigned(std::max<uint64_t>(64, std::min<uint64_t>(512, (1ull << 27) / std::max<uint64_t>(N, 1)))));
+    if (rc == HM_OK) rc = tmp.get(&acc, kAccN);
+    if (rc == HM_OK) rc = tmp.get(&tv, N);
+    if (rc == HM_OK) rc = tmp.get(&tri_e, n2);
+    if (rc == HM_OK) rc = tmp.get(&cnt, uint64_t(g) * N);
+    if (rc == HM_OK) rc = tmp.get(&touched, uint64_t(g) * N);
+    if (rc == HM_OK) rc = tmp.get(&outdeg, N);
+    if (rc == HM_OK) rc = tmp.get(&dmax, 1);
+    if (rc == HM_OK) rc = fill_u64(acc, 0, kAccN, st);
+    if (rc == HM_OK) rc = fill_u64(tv, 0, N, st);
+    if (rc == HM_OK) rc = fill_u32(cnt, 0, uint64_t(g) * N, st);
+    if (rc == HM_OK) rc = fill_u32(dmax, 0, 1, st);
+    if (rc == HM_OK && n2) {
+      k_sp_edge_tri<<<grid_cap(n2, kWavesPerBlock, 2048), kThreads, 0, st>>>(v, n2, tri_e, tv, acc);
+      k_es_widen<<<grid_cap(n2, 256, 2048), 256, 0, st>>>(tri_e, n2, es);
+      k_es_sums<<<grid_cap(n2, kWavesPerBlock, 2048), kThreads, 0, st>>>(v, n2, H->g2_eid, tri_e, es + 3 * n2,
+                                                                         es + 4 * n2, es + 5 * n2);
+      k_sp_c4<true><<<g, kThreads, 0, st>>>(v, cnt, touched, acc, H->g2_eid, es + 2 * n2);
+      k_sp_outdeg<<<grid_cap(N, 256, 1024), 256, 0, st>>>(v, outdeg);
+      if (hipGetLastError() != hipSuccess) rc = HM_EDEVICE;
+      if (rc == HM_OK) rc = max_u32(outdeg, N, dmax, st);
+      uint32_t cap = 0;
+      if (rc == HM_OK && hipMemcpyAsync(&cap, dmax, sizeof(uint32_t), hipMemcpyDeviceToHost, st) != hipSuccess)
+        rc = HM_EDEVICE;
+      if (rc == HM_OK && hipStreamSynchronize(st) != hipSuccess) rc = HM_EDEVICE;
+      cap = std::max<uint32_t>(cap, 1);
+      const unsigned gk = grid_cap(n2, kWavesPerBlock, 1024);
+      if (rc == HM_OK) rc = tmp.get(&wlist, uint64_t(gk) * kWavesPerBlock * cap * 2);
+      if (rc == HM_OK) {
+        k_sp_k4<true><<<gk, kThreads, 0, st>>>(v, n2, cap, wlist, acc, H->g2_eid, es + 1 * n2);
+        if (hipGetLastError() != hipSuccess) rc = HM_EDEVICE;
+      }
+    }
+    if (rc == HM_OK && hipStreamSynchronize(st) != hipSuccess) rc = HM_EDEVICE;
+  }
+  if (rc != HM_OK) {
+    dfree(p_es);
+    return rc;
+  }
+  H->es = es;
+  return HM_OK;
+}
 
 // The pair -> 3-node hyperedge index of H, built on first use.
 int ensure_pair_links(hm_graph* H, hipStream_t st) {
@@ -371,7 +586,7 @@ int count_sparse(const hm_graph* H, int k, hipStream_t st) {
     HM_TRY(fill_u32(cnt, 0, uint64_t(g) * H->n_nodes, st));
     {
       ProfileScope ps("k_sp_c4", st);
-      k_sp_c4<<<g, kThreads, 0, st>>>(v, cnt, touched, acc);
+      k_sp_c4<false><<<g, kThreads, 0, st>>>(v, cnt, touched, acc, nullptr, nullptr);
     }
     // 4-cliques
     uint32_t *outdeg = nullptr, *dmax = nullptr;
@@ -388,7 +603,7 @@ int count_sparse(const hm_graph* H, int k, hipStream_t st) {
     HM_TRY(tmp.get(&wlist, uint64_t(gk) * kWavesPerBlock * std::max<uint32_t>(cap, 1)));
     {
       ProfileScope ps("k_sp_k4", st);
-      k_sp_k4<<<gk, kThreads, 0, st>>>(v, n2, std::max<uint32_t>(cap, 1), wlist, acc);
+      k_sp_k4<false><<<gk, kThreads, 0, st>>>(v, n2, std::max<uint32_t>(cap, 1), wlist, acc, nullptr, nullptr);
     }
     HM_HIP(hipGetLastError());
   }

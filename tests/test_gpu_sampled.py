@@ -102,19 +102,34 @@ def test_facetoface_order3_paper_allocation(hm):
     assert np.array_equal(est.cpu().numpy(), want_est)
 
 
+@pytest.mark.parametrize("bit_rows", [True, False], ids=["bits", "hash"])
 @pytest.mark.parametrize("name,k,maker", [("facetoface_N200_E2000", 3, W.cfg0_facetoface_k3),
-                                          ("facetoface_N400_E30000", 4, W.cfg1_facetoface_k4)])
-def test_census_reproduces_exact(hm, name, k, maker):
+                                          ("facetoface_N400_E30000", 4, W.cfg1_facetoface_k4),
+                                          ("communication_scaled_0.004", 4,
+                                           lambda seed: W.scaled_communication(0.004, seed))])
+def test_census_reproduces_exact(hm, name, k, maker, bit_rows):
     """Every hyperedge sampled once: raw = countmax * exact and the estimate is the exact count."""
     h = maker(0)
     exact = _golden(name, k)
-    with _graph(hm, h) as g:
+    with _graph(hm, h, bit_rows) as g:
         st = g.stats()
         samples = {j: np.arange(st[f"n{j}"]) for j in range(2, k + 1)}
         est, raw = hm.count_sampled_indices(g, k, samples)
         countmax = np.array([hm.hm_class_info(k, c)[2] for c in range(len(exact))])
     assert np.array_equal(raw.cpu().numpy(), exact * countmax)
     assert np.array_equal(est.cpu().numpy(), exact.astype(np.float32))
+
+
+@pytest.mark.parametrize("bit_rows", [True, False], ids=["bits", "hash"])
+def test_heavy_tailed_matches_oracle(hm, bit_rows):
+    """Hubs, pairs inside many 3-node hyperedges: raw counts of 20% draws against the oracle."""
+    h = W.scaled_communication(0.004, 0)
+    nh = core.normalise(h)
+    want_raw, want_est, _, _ = _oracle_sampled(nh, 4, 0.2, 31)
+    with _graph(hm, h, bit_rows) as g:
+        est, raw = hm.count_sampled(g, 4, 0.2, 31, 0)
+    assert np.array_equal(raw.cpu().numpy(), want_raw)
+    assert np.array_equal(est.cpu().numpy(), want_est)
 
 
 def test_explicit_indices_match_oracle(hm):
