@@ -75,16 +75,48 @@ __device__ inline uint32_t row_count(const View& v, uint32_t s, uint32_t x) {
   return wave_sum_u32(n);
 }
 
-template <bool OWN>
-__device__ void b4_sparse(const View& v, const PairLinks& pl, uint32_t a, uint32_t b, uint32_t c, const uint8_t* lut,
-                          unsigned long long* h_main, unsigned long long* h_sub) {
+// The hyperedge e = {a<b<c} with its pairwise pattern and the ranges of its
+// exceptional nodes: slot 0..2 the pair index entries of {a,b}, {a,c},
+// {b,c}; slot 3 the 4-node hyperedges of the member with the fewest of them.
+struct B4Ctx {
+  uint32_t a, b, c, base_p;
+  // named scalars, not arrays: a dynamically indexed array would live in scratch
+  uint64_t lo0, lo1, lo2, lo3, len0, len1, len2, len3, total;
+};
+
+__device__ __forceinline__ B4Ctx b4_ctx(const View& v, const PairLinks& pl, uint32_t a, uint32_t b, uint32_t c) {
+  B4Ctx x;
+  x.a = a;
+  x.b = b;
+  x.c = c;
+  x.base_p = has2(v.hs2, a, b) | (has2(v.hs2, a, c) << 1) | (has2(v.hs2, b, c) << 2) | (1u << 3);
+  const unsigned long long kab = ((unsigned long long)a << 32) | b, kac = ((unsigned long long)a << 32) | c,
+                           kbc = ((unsigned long long)b << 32) | c;
+  x.lo0 = pl_lower(pl, kab);
+  x.len0 = pl_lower(pl, kab + 1) - x.lo0;
+  x.lo1 = pl_lower(pl, kac);
+  x.len1 = pl_lower(pl, kac + 1) - x.lo1;
+  x.lo2 = pl_lower(pl, kbc);
+  x.len2 = pl_lower(pl, kbc + 1) - x.lo2;
+  const uint32_t fa = v.i4_off[a + 1] - v.i4_off[a], fb = v.i4_off[b + 1] - v.i4_off[b],
+                 fc = v.i4_off[c + 1] - v.i4_off[c];
+  const uint32_t m4 = (fa <= fb && fa <= fc) ? a : (fb <= fc ? b : c);
+  x.lo3 = v.i4_off[m4];
+  x.len3 = v.i4_off[m4 + 1] - x.lo3;
+  x.total = x.len0 + x.len1 + x.len2 + x.len3;
+  return x;
+}
+
+// Number of nodes v outside e per pairwise combination (av | bv<<1 | cv<<2),
+// exceptional ones included, valid in every lane: the smallest row against
+// the other two members and the smaller of the remaining two rows against the
+// last member, in one lane-strided range; inclusion-exclusion with the
+// members of e removed.
+__device__ __forceinline__ void b4_combo_counts(const View& v, const B4Ctx& x, uint32_t n[8]) {
   const int lane = threadIdx.x & (kWave - 1);
-  const uint32_t pab = has2(v.hs2, a, b), pac = has2(v.hs2, a, c), pbc = has2(v.hs2, b, c);
-  const uint32_t base_p = pab | (pac << 1) | (pbc << 2) | (1u << 3);
+  const uint32_t a = x.a, b = x.b, c = x.c;
+  const uint32_t pab = x.base_p & 1u, pac = (x.base_p >> 1) & 1u, pbc = (x.base_p >> 2) & 1u;
   const uint32_t da = deg2_of(v, a), db = deg2_of(v, b), dc = deg2_of(v, c);
-  // intersections, in one lane-strided range: the smallest row against the
-  // other two members, then the smaller of the remaining two rows against the
-  // last member
   uint32_t r1, x1, y1, r2, x2;   // rows walked and the members they are probed against
   if (da <= db && da <= dc) {
     r1 = a; x1 = b; y1 = c;
@@ -97,99 +129,140 @@ __device__ void b4_sparse(const View& v, const PairLinks& pl, uint32_t a, uint32
     r2 = da <= db ? a : b; x2 = da <= db ? b : a;
   }
   uint32_t n1x = 0, n1y = 0, n1xy = 0, n2x = 0;
-  {
-    const uint32_t b1 = v.g2_off[r1], l1 = v.g2_off[r1 + 1] - b1;
-    const uint32_t b2 = v.g2_off[r2], l2 = v.g2_off[r2 + 1] - b2;
-    for (uint32_t t = lane; t < l1 + l2; t += kWave) {
-      if (t < l1) {
-        const uint32_t z = v.g2_adj[b1 + t];
-        const uint32_t hx = has2(v.hs2, x1, z), hy = has2(v.hs2, y1, z);
-        n1x += hx;
-        n1y += hy;
-        n1xy += hx & hy;
-      } else {
-        n2x += has2(v.hs2, x2, v.g2_adj[b2 + (t - l1)]);
-      }
+  const uint32_t b1 = v.g2_off[r1], l1 = v.g2_off[r1 + 1] - b1;
+  const uint32_t b2 = v.g2_off[r2], l2 = v.g2_off[r2 + 1] - b2;
+  for (uint32_t t = lane; t < l1 + l2; t += kWave) {
+    if (t < l1) {
+      const uint32_t z = v.g2_adj[b1 + t];
+      const uint32_t hx = has2(v.hs2, x1, z), hy = has2(v.hs2, y1, z);
+      n1x += hx;
+      n1y += hy;
+      n1xy += hx & hy;
+    } else {
+      n2x += has2(v.hs2, x2, v.g2_adj[b2 + (t - l1)]);
     }
-    n1x = wave_sum_u32(n1x);
-    n1y = wave_sum_u32(n1y);
-    n1xy = wave_sum_u32(n1xy);
-    n2x = wave_sum_u32(n2x);
   }
-  // codeg of each pair of e, and the triple intersection
+  n1x = wave_sum_u32(n1x);
+  n1y = wave_sum_u32(n1y);
+  n1xy = wave_sum_u32(n1xy);
+  n2x = wave_sum_u32(n2x);
   const uint32_t tri = n1xy;
   uint32_t cab, cac, cbc;
   if (r1 == a) { cab = n1x; cac = n1y; cbc = n2x; }
   else if (r1 == b) { cab = n1x; cbc = n1y; cac = n2x; }
   else { cac = n1x; cbc = n1y; cab = n2x; }
-  // exceptional nodes, each once, by the first hyperedge that makes it one
-  // (slot 0..2: {a,b,v}, {a,c,v}, {b,c,v} through the pair index; slot 3:
-  // {a,b,c,v} from the member with the fewest 4-node hyperedges), all slots
-  // in one lane-strided range; per lane, the number of them in each pairwise
-  // combination
-  uint64_t lo[4], len[4];
-  for (int slot = 0; slot < 3; ++slot) {
+  const uint32_t sa = da - pab - pac, sb = db - pab - pbc, sc = dc - pac - pbc;
+  const uint32_t iab = cab - pac * pbc, iac = cac - pab * pbc, ibc = cbc - pab * pac;
+  n[0] = 0;
+  n[7] = tri;
+  n[3] = iab - tri;
+  n[5] = iac - tri;
+  n[6] = ibc - tri;
+  n[1] = sa - n[3] - n[5] - n[7];
+  n[2] = sb - n[3] - n[6] - n[7];
+  n[4] = sc - n[5] - n[6] - n[7];
+}
+
+// The exceptional node at flat position t of the ranges of x, each node
+// once (by the first hyperedge that makes it exceptional).  Returns 0 when the
+// position holds none; else bit 4 set, its pairwise combination in bits 0..2,
+// bit 3 set when its set counts (not a 4-node hyperedge and, with OWN, e its
+// smallest 3-node hyperedge), with the set's pattern in *pat.
+template <bool OWN>
+__device__ __forceinline__ uint32_t b4_exception(const View& v, const PairLinks& pl, const B4Ctx& x, uint64_t t,
+                                        uint32_t* pat) {
+  const uint32_t a = x.a, b = x.b, c = x.c;
+  // slot and offset of t, with constant indices only (registers)
+  int slot;
+  uint64_t p;
+  if (t < x.len0) {
+    slot = 0;
+    p = x.lo0 + t;
+  } else if (t < x.len0 + x.len1) {
+    slot = 1;
+    p = x.lo1 + (t - x.len0);
+  } else if (t < x.len0 + x.len1 + x.len2) {
+    slot = 2;
+    p = x.lo2 + (t - x.len0 - x.len1);
+  } else {
+    slot = 3;
+    p = x.lo3 + (t - x.len0 - x.len1 - x.len2);
+  }
+  uint32_t y;
+  uint32_t abv = 0, acv = 0, bcv = 0, quad = 0;
+  if (slot < 3) {
     const uint32_t q0 = slot < 2 ? a : b, q1 = slot == 0 ? b : c;
-    const unsigned long long key = ((unsigned long long)q0 << 32) | q1;
-    lo[slot] = pl_lower(pl, key);
-    len[slot] = pl_lower(pl, key + 1) - lo[slot];
-  }
-  {
-    const uint32_t fa = v.i4_off[a + 1] - v.i4_off[a], fb = v.i4_off[b + 1] - v.i4_off[b],
-                   fc = v.i4_off[c + 1] - v.i4_off[c];
-    const uint32_t m4 = (fa <= fb && fa <= fc) ? a : (fb <= fc ? b : c);
-    lo[3] = v.i4_off[m4];
-    len[3] = v.i4_off[m4 + 1] - lo[3];
-  }
-  const uint64_t total = len[0] + len[1] + len[2] + len[3];
-  uint32_t dn1 = 0, dn2 = 0, dn3 = 0, dn4 = 0, dn5 = 0, dn6 = 0, dn7 = 0;
-  for (uint64_t t = lane; t < total; t += kWave) {
-    int slot = 0;
-    uint64_t off = t;
-    while (off >= len[slot]) {
-      off -= len[slot];
-      ++slot;
-    }
-    const uint64_t p = lo[slot] + off;
-    uint32_t x;
-    uint32_t abv = 0, acv = 0, bcv = 0, quad = 0;
-    if (slot < 3) {
-      const uint32_t q0 = slot < 2 ? a : b, q1 = slot == 0 ? b : c;
-      const uint32_t* f = v.e3 + 3ull * pl.edge[p];
-      x = f[0] ^ f[1] ^ f[2] ^ q0 ^ q1;
-      if (x == a || x == b || x == c) continue;   // e itself
-      if (slot == 0) {
-        abv = 1;
-      } else if (slot == 1) {
-        if (has3(v.hs3, a, b, x)) continue;
-        acv = 1;
-      } else {
-        if (has3(v.hs3, a, b, x) || has3(v.hs3, a, c, x)) continue;
-        bcv = 1;
-      }
+    const uint32_t* f = v.e3 + 3ull * pl.edge[p];
+    y = f[0] ^ f[1] ^ f[2] ^ q0 ^ q1;
+    if (y == a || y == b || y == c) return 0;   // e itself
+    if (slot == 0) {
+      abv = 1;
+    } else if (slot == 1) {
+      if (has3(v.hs3, a, b, y)) return 0;
+      acv = 1;
     } else {
-      const uint32_t* f = v.e4 + 4ull * v.i4_idx[p];
-      const uint32_t f0 = f[0], f1 = f[1], f2 = f[2], f3 = f[3];
-      const uint32_t hit = uint32_t(f0 == a || f0 == b || f0 == c) + uint32_t(f1 == a || f1 == b || f1 == c) +
-                           uint32_t(f2 == a || f2 == b || f2 == c) + uint32_t(f3 == a || f3 == b || f3 == c);
-      if (hit != 3) continue;
-      x = f0 ^ f1 ^ f2 ^ f3 ^ a ^ b ^ c;
-      if (has3(v.hs3, a, b, x) || has3(v.hs3, a, c, x) || has3(v.hs3, b, c, x)) continue;
-      quad = 1;
+      if (has3(v.hs3, a, b, y) || has3(v.hs3, a, c, y)) return 0;
+      bcv = 1;
     }
-    // fill-in of e u {x}
-    if (slot <= 0) acv = has3(v.hs3, a, c, x);
-    if (slot <= 1) bcv = has3(v.hs3, b, c, x);
-    if (slot < 3) {
-      uint32_t s0 = a, s1 = b, s2 = c, s3 = x;
-      // ascending 4-tuple for the 4-node probe
-      if (s3 < s2) { const uint32_t tt = s2; s2 = s3; s3 = tt; }
-      if (s2 < s1) { const uint32_t tt = s1; s1 = s2; s2 = tt; }
-      if (s1 < s0) { const uint32_t tt = s0; s0 = s1; s1 = tt; }
-      quad = set128_has(v.hs4, key4(s0, s1, s2, s3));
-    }
-    const uint32_t av = has2(v.hs2, a, x), bv = has2(v.hs2, b, x), cv = has2(v.hs2, c, x);
-    const uint32_t combo = av | (bv << 1) | (cv << 2);
+  } else {
+    const uint32_t* f = v.e4 + 4ull * v.i4_idx[p];
+    const uint32_t f0 = f[0], f1 = f[1], f2 = f[2], f3 = f[3];
+    const uint32_t hit = uint32_t(f0 == a || f0 == b || f0 == c) + uint32_t(f1 == a || f1 == b || f1 == c) +
+                         uint32_t(f2 == a || f2 == b || f2 == c) + uint32_t(f3 == a || f3 == b || f3 == c);
+    if (hit != 3) return 0;
+    y = f0 ^ f1 ^ f2 ^ f3 ^ a ^ b ^ c;
+    if (has3(v.hs3, a, b, y) || has3(v.hs3, a, c, y) || has3(v.hs3, b, c, y)) return 0;
+    quad = 1;
+  }
+  // fill-in of e u {y}
+  if (slot <= 0) acv = has3(v.hs3, a, c, y);
+  if (slot <= 1) bcv = has3(v.hs3, b, c, y);
+  if (slot < 3) {
+    uint32_t s0 = a, s1 = b, s2 = c, s3 = y;
+    // ascending 4-tuple for the 4-node probe
+    if (s3 < s2) { const uint32_t tt = s2; s2 = s3; s3 = tt; }
+    if (s2 < s1) { const uint32_t tt = s1; s1 = s2; s2 = tt; }
+    if (s1 < s0) { const uint32_t tt = s0; s0 = s1; s1 = tt; }
+    quad = set128_has(v.hs4, key4(s0, s1, s2, s3));
+  }
+  const uint32_t av = has2(v.hs2, a, y), bv = has2(v.hs2, b, y), cv = has2(v.hs2, c, y);
+  const uint32_t combo = av | (bv << 1) | (cv << 2);
+  bool counted = !quad;   // a 4-node hyperedge: counted on its own, or larger than a sampled 3-node one
+  if (OWN && counted) {
+    // e must be the smallest 3-node hyperedge of the set
+    uint32_t t0 = a, t1 = b, t2 = y;
+    if (abv) { sort3(t0, t1, t2); counted = counted && !tri_less(t0, t1, t2, a, b, c); }
+    t0 = a; t1 = c; t2 = y;
+    if (acv) { sort3(t0, t1, t2); counted = counted && !tri_less(t0, t1, t2, a, b, c); }
+    t0 = b; t1 = c; t2 = y;
+    if (bcv) { sort3(t0, t1, t2); counted = counted && !tri_less(t0, t1, t2, a, b, c); }
+  }
+  *pat = x.base_p | (av << 4) | (bv << 5) | (abv << 6) | (cv << 7) | (acv << 8) | (bcv << 9);
+  return 16u | (counted ? 8u : 0u) | combo;
+}
+
+// The combination pattern of e u {v} for a non-exceptional v.
+__device__ inline uint32_t b4_combo_pattern(const B4Ctx& x, uint32_t cmb) {
+  return x.base_p | ((cmb & 1u) << 4) | (((cmb >> 1) & 1u) << 5) | ((cmb >> 2) << 7);
+}
+
+// Exact counting (OWN = true) and the bit-free sampler's inline path: one
+// wavefront per hyperedge.
+template <bool OWN>
+__device__ void b4_sparse(const View& v, const PairLinks& pl, uint32_t a, uint32_t b, uint32_t c, const uint8_t* lut,
+                          unsigned long long* h_main, unsigned long long* h_sub) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const B4Ctx x = b4_ctx(v, pl, a, b, c);
+  uint32_t n[8];
+  b4_combo_counts(v, x, n);
+  // exceptional nodes, in one lane-strided range; per lane, the number of
+  // them in each pairwise combination
+  uint32_t dn1 = 0, dn2 = 0, dn3 = 0, dn4 = 0, dn5 = 0, dn6 = 0, dn7 = 0;
+  for (uint64_t t = lane; t < x.total; t += kWave) {
+    uint32_t pat;
+    const uint32_t r = b4_exception<OWN>(v, pl, x, t, &pat);
+    if (!r) continue;
+    const uint32_t combo = r & 7u;
     dn1 += combo == 1;
     dn2 += combo == 2;
     dn3 += combo == 3;
@@ -197,19 +270,7 @@ __device__ void b4_sparse(const View& v, const PairLinks& pl, uint32_t a, uint32
     dn5 += combo == 5;
     dn6 += combo == 6;
     dn7 += combo == 7;
-    if (quad) continue;   // a 4-node hyperedge: counted on its own, or larger than a sampled 3-node one
-    if (OWN) {
-      // e must be the smallest 3-node hyperedge of the set
-      uint32_t t0 = a, t1 = b, t2 = x;
-      bool owned = true;
-      if (abv) { sort3(t0, t1, t2); owned = owned && !tri_less(t0, t1, t2, a, b, c); }
-      t0 = a; t1 = c; t2 = x;
-      if (acv) { sort3(t0, t1, t2); owned = owned && !tri_less(t0, t1, t2, a, b, c); }
-      t0 = b; t1 = c; t2 = x;
-      if (bcv) { sort3(t0, t1, t2); owned = owned && !tri_less(t0, t1, t2, a, b, c); }
-      if (!owned) continue;
-    }
-    const uint32_t pat = base_p | (av << 4) | (bv << 5) | (abv << 6) | (cv << 7) | (acv << 8) | (bcv << 9);
+    if (!(r & 8u)) continue;
     atomicAdd(&h_main[lut[pat]], 1ull);
     if (OWN) {
       const uint8_t g = lut[pat & kPairBits4];
@@ -224,17 +285,6 @@ __device__ void b4_sparse(const View& v, const PairLinks& pl, uint32_t a, uint32
   dn6 = wave_sum_u32(dn6);
   dn7 = wave_sum_u32(dn7);
   if (lane == 0) {
-    // inclusion-exclusion over N(a), N(b), N(c) with the members of e removed
-    const uint32_t sa = da - pab - pac, sb = db - pab - pbc, sc = dc - pac - pbc;
-    const uint32_t iab = cab - pac * pbc, iac = cac - pab * pbc, ibc = cbc - pab * pac;
-    uint32_t n[8];
-    n[7] = tri;
-    n[3] = iab - tri;
-    n[5] = iac - tri;
-    n[6] = ibc - tri;
-    n[1] = sa - n[3] - n[5] - n[7];
-    n[2] = sb - n[3] - n[6] - n[7];
-    n[4] = sc - n[5] - n[6] - n[7];
     n[1] -= dn1;
     n[2] -= dn2;
     n[3] -= dn3;
@@ -245,7 +295,7 @@ __device__ void b4_sparse(const View& v, const PairLinks& pl, uint32_t a, uint32
 #pragma unroll
     for (uint32_t cmb = 1; cmb < 8; ++cmb) {
       if (!n[cmb]) continue;
-      const uint32_t pat = base_p | ((cmb & 1u) << 4) | (((cmb >> 1) & 1u) << 5) | ((cmb >> 2) << 7);
+      const uint32_t pat = b4_combo_pattern(x, cmb);
       atomicAdd(&h_main[lut[pat]], (unsigned long long)n[cmb]);
       if (OWN) {
         const uint8_t g = lut[pat & kPairBits4];

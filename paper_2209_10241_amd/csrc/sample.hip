@@ -71,22 +71,87 @@ __device__ void sample_j4(const View& v, const Draws& d, uint32_t part, uint32_t
   }
 }
 
+// Work chunks of heavy samples (without bit rows), drained by every
+// workgroup of a second launch so that one sample's work spreads over many.
+enum : uint32_t { kJobNone = 0, kJobPairT = 1, kJobPairR = 2, kJobTriple = 3, kJobPairS = 4, kJobPairQ = 5 };
+constexpr uint32_t kChunkT = 64;    // nodes of T per chunk
+constexpr uint32_t kChunkR = 256;   // correction items per chunk
+constexpr uint32_t kChunkX = 512;   // exception positions per chunk
+constexpr uint32_t kChunkH = 1024;  // hyperedges at s (3-node) or holding e (4-node) per chunk
+
+struct Queue {
+  uint4* job;                   // {kind, sample, first, last}
+  unsigned long long cap;
+  unsigned long long* tail;     // reserved entries (may pass cap: those are done in place)
+  unsigned long long* head;     // claimed entries
+  uint32_t* tcls;               // per pair sample: |T n A_q|, q = 1..3
+};
+
+// Reserve n entries; returns the first, or ~0 when they do not fit (the
+// caller then does the work in place; entries it reserved below cap are
+// marked empty).
+__device__ inline unsigned long long queue_reserve(const Queue& q, uint32_t n) {
+  const unsigned long long base = atomicAdd(q.tail, (unsigned long long)n);
+  if (base + n <= q.cap) return base;
+  for (unsigned long long e = base; e < q.cap && e < base + n; ++e) q.job[e] = make_uint4(kJobNone, 0, 0, 0);
+  return ~0ull;
+}
+
 // j = 3 at order 4: the neighbourhood of the sampled 3-node hyperedge.  One
-// wavefront per sample.
+// wavefront per sample.  Without bit rows the exceptional nodes go to the
+// work queue when they span more than one chunk.
+__device__ __forceinline__ void j3_exceptions(const View& v, const PairLinks& pl, const B4Ctx& x, uint64_t first,
+                                     uint64_t last, uint32_t lane, uint32_t stride, const uint8_t* lut,
+                                     unsigned long long* h) {
+  for (uint64_t t = first + lane; t < last; t += stride) {
+    uint32_t pat;
+    const uint32_t r = b4_exception<false>(v, pl, x, t, &pat);
+    if (!r) continue;
+    if (r & 7u) {
+      const uint8_t cc = lut[b4_combo_pattern(x, r & 7u)];
+      atomicAdd(&h[cc], ~0ull);   // counted among its combination: minus one
+    }
+    if (r & 8u) atomicAdd(&h[lut[pat]], 1ull);
+  }
+}
+
 template <bool BITS>
-__device__ void sample_j3_k4(const View& v, const PairLinks& pl, const Draws& d, uint32_t part, uint32_t n_parts,
-                             B4Scratch* scratch, const uint8_t* lut, unsigned long long* h_lds,
+__device__ void sample_j3_k4(const View& v, const PairLinks& pl, const Queue& q, const Draws& d, uint32_t part,
+                             uint32_t n_parts, B4Scratch* scratch, const uint8_t* lut, unsigned long long* h_lds,
                              unsigned long long* rows) {
   const int wv = threadIdx.x / kWave;
+  const uint32_t lane = threadIdx.x & (kWave - 1);
   for (uint64_t s = uint64_t(part) * kWavesPerBlock + wv; s < d.S[3]; s += uint64_t(n_parts) * kWavesPerBlock) {
     const uint64_t i = d.at(3, s);
     if (i >= d.n[3]) continue;
     const uint32_t a = v.e3[3 * i], b = v.e3[3 * i + 1], c = v.e3[3 * i + 2];
-    if constexpr (BITS)
+    unsigned long long* h = row_or(rows, s, h_lds);
+    if constexpr (BITS) {
       b4_edge_bits<false>(a, b, c, v.e3, v.e4, v.i3_off, v.i3_idx, v.i4_off, v.i4_idx, v.bits, v.W, scratch[wv], lut,
-                          row_or(rows, s, h_lds), nullptr);
-    else
-      b4_sparse<false>(v, pl, a, b, c, lut, row_or(rows, s, h_lds), nullptr);
+                          h, nullptr);
+    } else {
+      const B4Ctx x = b4_ctx(v, pl, a, b, c);
+      uint32_t n[8];
+      b4_combo_counts(v, x, n);
+      if (lane == 0) {
+#pragma unroll
+        for (uint32_t cmb = 1; cmb < 8; ++cmb)
+          if (n[cmb]) atomicAdd(&h[lut[b4_combo_pattern(x, cmb)]], (unsigned long long)n[cmb]);
+      }
+      const uint64_t jobs = (x.total + kChunkX - 1) / kChunkX;
+      unsigned long long base = ~0ull;
+      if (q.job && jobs > 1) {
+        if (lane == 0) base = queue_reserve(q, uint32_t(jobs));
+        base = __shfl(base, 0, kWave);
+      }
+      if (base == ~0ull) {
+        j3_exceptions(v, pl, x, 0, x.total, lane, kWave, lut, h);
+      } else {
+        for (uint64_t k = lane; k < jobs; k += kWave)
+          q.job[base + k] = make_uint4(kJobTriple, uint32_t(s), uint32_t(k * kChunkX),
+                                       uint32_t(min<uint64_t>((k + 1) * kChunkX, x.total)));
+      }
+    }
   }
 }
 
@@ -106,23 +171,23 @@ struct NodeStats {
 // (below): e u {x, y} with x, y outside X = e u T, T = {t : {s,o,t} is a
 // 3-node hyperedge}, connected through pairs, and no larger hyperedge inside.
 // Nodes z outside e fall in classes by adjacency to (s, o): 1 = s only, 2 = o
-// only, 3 = both; A_1, A_2, A_3 partition A = N(s) u N(o) \ e.  All work is
-// done from s's side:
-//   first term without T: class sizes |A_3| = t_e, |A_1| = d_s - 1 - t_e,
-//     |A_2| = d_o - 1 - t_e; pairs of A joined by a pair, per class pair, from
-//     the triangles at s and o, and for each neighbour x of s the
-//     intersections of N(x) with N(s), N(o) and both; pairs of A not joined by
-//     complement; sets with y hanging off x alone from the neighbour-degree sums;
-//   pairs touching T are taken off through the rows of the nodes of T;
-//   second term: the 3-node hyperedges at s one by one, those at o from its
-//     8-bin pattern histogram (valid when neither other node meets s's side),
-//     corrected one by one for the 3-node hyperedges {o, y, z} where y or z is
-//     in N(s) u T or {s, y, z} is a 3-node hyperedge; the 4-node hyperedges
-//     holding e one by one.
-// One workgroup per sample.
+// only, 3 = both; A_1, A_2, A_3 partition A = N(s) u N(o) \ e.
+//   First term without T: class sizes |A_3| = t_e, |A_1| = d_s - 1 - t_e,
+//   |A_2| = d_o - 1 - t_e; pairs of A joined by a pair, per class pair, from
+//   the triangles at s and o and the per-pair statistics of e (4-cliques and
+//   4-cycles through e, triangle and degree sums over the common
+//   neighbours); pairs of A not joined by complement; sets with y hanging off
+//   x alone from the neighbour-degree sums.
+//   Pairs touching T come off through the rows of the nodes of T (as if every
+//   pair inside T were not joined, then corrected per joined pair).
+//   Second term: the 3-node hyperedges at s one by one, those at o from its
+//   8-bin pattern histogram (valid when neither other node meets s's side),
+//   corrected one by one for the 3-node hyperedges {o, y, z} where y or z is
+//   in N(s) u T or {s, y, z} is a 3-node hyperedge; the 4-node hyperedges
+//   holding e one by one.
+// One workgroup per sample; the walks over T and over the corrections go to
+// the work queue when longer than one chunk.
 struct J2SparseLds {
-  unsigned long long acc[8];   // |A_3|, sums for A_3: codeg(s,x)-1, codeg(o,x)-1, |N(x) n A_3|, deg; for A_1: codeg(o,x)-1
-  unsigned long long adj_tt[16];   // joined pairs inside T by (class, class), from both ends
   uint32_t tcls[4];
   // flat walks over up to 256 items, each with up to three row segments
   uint32_t pre[kThreads + 1];
@@ -130,21 +195,21 @@ struct J2SparseLds {
   uint32_t item[kThreads];
   uint32_t seg_base[kThreads][3];
   uint32_t seg_len[kThreads][3];
-  uint32_t cnt[kThreads][7];
+  uint32_t cnt[kThreads][11];
 };
 
-// Walk, for items [0, n) 256 at a time, the concatenated segments seg(i)
-// defines (up to three, each a start and a length), as one flat range over
-// the workgroup: body(slot, segment, position) for every position; then
+// Walk, for items [first, last) 256 at a time, the concatenated segments
+// seg(i) defines (up to three, each a start and a length), as one flat range
+// over the workgroup: body(slot, segment, position) for every position; then
 // fin(slot, item) once per item.  Every thread must call it.
 template <typename Seg, typename Body, typename Fin>
-__device__ void block_flat(uint32_t n, J2SparseLds& L, Seg seg, Body body, Fin fin) {
+__device__ void block_flat(uint32_t first, uint32_t last, J2SparseLds& L, Seg seg, Body body, Fin fin) {
   const uint32_t tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
-  for (uint32_t c0 = 0; c0 < n; c0 += kThreads) {
+  for (uint32_t c0 = first; c0 < last; c0 += kThreads) {
     uint32_t len = 0;
     L.seg_len[tid][0] = L.seg_len[tid][1] = L.seg_len[tid][2] = 0;
-    for (int q = 0; q < 7; ++q) L.cnt[tid][q] = 0;
-    if (c0 + tid < n) {
+    for (int q = 0; q < 11; ++q) L.cnt[tid][q] = 0;
+    if (c0 + tid < last) {
       seg(c0 + tid, L.seg_base[tid], L.seg_len[tid]);
       len = L.seg_len[tid][0] + L.seg_len[tid][1] + L.seg_len[tid][2];
     }
@@ -172,248 +237,345 @@ __device__ void block_flat(uint32_t n, J2SparseLds& L, Seg seg, Body body, Fin f
       body(lo, sg, L.seg_base[lo][sg] + k);
     }
     __syncthreads();
-    if (c0 + tid < n) fin(tid, c0 + tid);
+    if (c0 + tid < last) fin(tid, c0 + tid);
     __syncthreads();
   }
+}
+
+struct J2Ctx {
+  uint32_t e0, s, o, ds, dO;
+  uint64_t tlo, thi;
+  bool any_t;
+  unsigned long long na[4];
+};
+
+__device__ inline J2Ctx j2_ctx(const View& v, const PairLinks& pl, const unsigned long long* es, uint64_t n2,
+                               uint64_t i) {
+  J2Ctx c;
+  const uint32_t e0 = v.e2[2 * i], e1 = v.e2[2 * i + 1];
+  const uint32_t d0 = deg2_of(v, e0), d1 = deg2_of(v, e1);
+  c.e0 = e0;
+  c.s = d0 <= d1 ? e0 : e1;
+  c.o = d0 <= d1 ? e1 : e0;
+  c.ds = d0 <= d1 ? d0 : d1;
+  c.dO = d0 <= d1 ? d1 : d0;
+  const unsigned long long key = ((unsigned long long)e0 << 32) | e1;
+  c.tlo = pl.n ? pl_lower(pl, key) : 0;
+  c.thi = pl.n ? pl_lower(pl, key + 1) : 0;
+  c.any_t = c.thi > c.tlo;
+  const unsigned long long te = es[i];
+  c.na[0] = 0;
+  c.na[1] = c.ds - 1 - te;
+  c.na[2] = c.dO - 1 - te;
+  c.na[3] = te;
+  return c;
 }
 
 __device__ inline uint32_t j2_pat(uint32_t cx, uint32_t cy, uint32_t xy) {
   return 1u | ((cx & 1u) << 1) | ((cx >> 1) << 2) | ((cy & 1u) << 4) | ((cy >> 1) << 5) | (xy << 7);
 }
+__device__ inline void hsub(const uint8_t* lut, unsigned long long* h, uint32_t pat, unsigned long long n) {
+  const uint8_t c = lut[pat];
+  if (c != 0xFF && n) atomicAdd(&h[c], 0ull - n);
+}
+__device__ inline void hadd(const uint8_t* lut, unsigned long long* h, uint32_t pat, unsigned long long n) {
+  const uint8_t c = lut[pat];
+  if (c != 0xFF && n) atomicAdd(&h[c], n);
+}
+__device__ inline bool j2_in_t(const View& v, const J2Ctx& c, uint32_t y) {
+  return c.any_t && has3(v.hs3, c.s, c.o, y);
+}
+__device__ inline uint32_t j2_cls(const View& v, const J2Ctx& c, uint32_t y) {
+  return has2(v.hs2, c.s, y) | (has2(v.hs2, c.o, y) << 1);
+}
+__device__ inline uint32_t j2_t_node(const View& v, const PairLinks& pl, const J2Ctx& c, uint64_t p) {
+  const uint32_t* f = v.e3 + 3ull * pl.edge[p];
+  return f[0] ^ f[1] ^ f[2] ^ c.s ^ c.o;
+}
+// a pair {x, y} outside X whose set holds a larger hyperedge, taken off
+__device__ inline void j2_remove(const View& v, const J2Ctx& c, const uint8_t* lut, unsigned long long* h, uint32_t x,
+                                 uint32_t y) {
+  if (x == c.s || x == c.o || y == c.s || y == c.o || j2_in_t(v, c, x) || j2_in_t(v, c, y)) return;
+  hsub(lut, h,
+       1u | (has2(v.hs2, c.s, x) << 1) | (has2(v.hs2, c.o, x) << 2) | (has2(v.hs2, c.s, y) << 4) |
+           (has2(v.hs2, c.o, y) << 5) | (has2(v.hs2, x, y) << 7),
+       1);
+}
+// a 3-node hyperedge {o, y, z} as the histogram at o counts it
+__device__ inline uint32_t j2_agg_pat(const View& v, const J2Ctx& c, uint32_t y, uint32_t z) {
+  if (z < y) {
+    const uint32_t t = y;
+    y = z;
+    z = t;
+  }
+  return 1u | (has2(v.hs2, c.o, y) << 2) | (has2(v.hs2, c.o, z) << 5) | (has2(v.hs2, y, z) << 7);
+}
+__device__ inline bool j2_near_s(const View& v, const J2Ctx& c, uint32_t y) {
+  return has2(v.hs2, c.s, y) || j2_in_t(v, c, y);
+}
+
+// Pairs touching T, for the nodes t of T at positions [first, last) of its
+// index range.  The neighbours y of t outside e by class follow from
+// |N(t) n N(s)| and |N(t) n N(s) n N(o)| (the shorter of the two rows walked)
+// and |N(t) n N(o)| (likewise); those inside T from the shorter of N(t) and T
+// (all of them, and those after t, which take each joined pair inside T once).
+__device__ void j2_walk_t(const View& v, const PairLinks& pl, const J2Ctx& c, uint32_t tc1, uint32_t tc2, uint32_t tc3,
+                          uint32_t first, uint32_t last, J2SparseLds& L, const uint8_t* lut, unsigned long long* h) {
+  const uint32_t n_t = uint32_t(c.thi - c.tlo);
+  block_flat(
+      first, last, L,
+      [&](uint32_t j, uint32_t* base, uint32_t* len) {
+        const uint32_t t = j2_t_node(v, pl, c, c.tlo + j);
+        const uint32_t dt = deg2_of(v, t);
+        base[0] = dt <= c.ds ? v.g2_off[t] : v.g2_off[c.s];
+        len[0] = dt <= c.ds ? dt : c.ds;
+        base[1] = dt <= c.dO ? v.g2_off[t] : v.g2_off[c.o];
+        len[1] = dt <= c.dO ? dt : c.dO;
+        base[2] = dt <= n_t ? v.g2_off[t] : uint32_t(c.tlo);
+        len[2] = dt <= n_t ? dt : n_t;
+      },
+      [&](uint32_t slot, uint32_t sg, uint32_t pos) {
+        const uint32_t t = j2_t_node(v, pl, c, c.tlo + L.item[slot]);
+        const uint32_t dt = deg2_of(v, t);
+        if (sg == 0) {
+          const uint32_t z = v.g2_adj[pos];
+          const uint32_t hit = dt <= c.ds ? has2(v.hs2, c.s, z) : has2(v.hs2, t, z);
+          if (hit) {
+            atomicAdd(&L.cnt[slot][0], 1u);
+            if (has2(v.hs2, c.o, z)) atomicAdd(&L.cnt[slot][1], 1u);
+          }
+        } else if (sg == 1) {
+          const uint32_t z = v.g2_adj[pos];
+          if (dt <= c.dO ? has2(v.hs2, c.o, z) : has2(v.hs2, t, z)) atomicAdd(&L.cnt[slot][2], 1u);
+        } else {
+          uint32_t y;
+          if (dt <= n_t) {
+            y = v.g2_adj[pos];
+            if (y == c.s || y == c.o || !j2_in_t(v, c, y)) return;
+          } else {
+            y = j2_t_node(v, pl, c, pos);
+            if (y == t || !has2(v.hs2, t, y)) return;
+          }
+          const uint32_t cy = j2_cls(v, c, y);
+          atomicAdd(&L.cnt[slot][3 + cy], 1u);
+          if (y > t) atomicAdd(&L.cnt[slot][7 + cy], 1u);
+        }
+      },
+      [&](uint32_t slot, uint32_t j) {
+        const uint32_t t = j2_t_node(v, pl, c, c.tlo + j);
+        const uint32_t ts = has2(v.hs2, c.s, t), to = has2(v.hs2, c.o, t);
+        const uint32_t ct = ts | (to << 1);
+        const uint32_t dt = deg2_of(v, t);
+        const uint32_t a_s = L.cnt[slot][0], a_so = L.cnt[slot][1], a_o = L.cnt[slot][2];
+        const uint32_t c3 = a_so, c1 = a_s - to - a_so, c2 = a_o - ts - a_so;
+        const uint32_t c0 = dt - ts - to - c1 - c2 - c3;
+        // neighbours outside T by class
+        const unsigned long long m0 = c0 - L.cnt[slot][3], m1 = c1 - L.cnt[slot][4], m2 = c2 - L.cnt[slot][5],
+                                 m3 = c3 - L.cnt[slot][6];
+        if (ct) {
+          hsub(lut, h, j2_pat(ct, 1, 1), m1);
+          hsub(lut, h, j2_pat(ct, 2, 1), m2);
+          hsub(lut, h, j2_pat(ct, 3, 1), m3);
+          hsub(lut, h, j2_pat(ct, 0, 1), m0);
+          // pairs {t, y}, y in A outside T, not joined
+          hsub(lut, h, j2_pat(ct, 1, 0), c.na[1] - tc1 - m1);
+          hsub(lut, h, j2_pat(ct, 2, 0), c.na[2] - tc2 - m2);
+          hsub(lut, h, j2_pat(ct, 3, 0), c.na[3] - tc3 - m3);
+        } else {
+          hsub(lut, h, j2_pat(1, 0, 1), m1);
+          hsub(lut, h, j2_pat(2, 0, 1), m2);
+          hsub(lut, h, j2_pat(3, 0, 1), m3);
+        }
+        // joined pairs {t, y} inside T, y after t: they were taken off as not
+        // joined (both in A) or not at all (y hanging off t or t off y)
+#pragma unroll
+        for (uint32_t cy = 0; cy < 4; ++cy) {
+          const unsigned long long k = L.cnt[slot][7 + cy];
+          if (!k) continue;
+          if (ct && cy) {
+            hadd(lut, h, j2_pat(ct, cy, 0), k);
+            hsub(lut, h, j2_pat(ct, cy, 1), k);
+          } else if (ct || cy) {
+            hsub(lut, h, j2_pat(ct | cy, 0, 1), k);
+          }
+        }
+      });
+}
+
+// Corrections for the 3-node hyperedges {o, y, z} with y in N(s) u T, for the
+// items [first, last) of the list N(s) then T (a node of T that is also a
+// neighbour of s taken once; each hyperedge from the smaller of y, z when both
+// qualify).
+__device__ void j2_walk_r(const View& v, const PairLinks& pl, const J2Ctx& c, uint32_t first, uint32_t last,
+                          J2SparseLds& L, const uint8_t* lut, unsigned long long* h) {
+  const uint32_t sb = v.g2_off[c.s];
+  auto y_of = [&](uint32_t j) { return j < c.ds ? v.g2_adj[sb + j] : j2_t_node(v, pl, c, c.tlo + (j - c.ds)); };
+  block_flat(
+      first, last, L,
+      [&](uint32_t j, uint32_t* base, uint32_t* len) {
+        const uint32_t y = y_of(j);
+        if (y == c.o || (j >= c.ds && has2(v.hs2, c.s, y))) return;
+        const unsigned long long ky =
+            y < c.o ? (((unsigned long long)y << 32) | c.o) : (((unsigned long long)c.o << 32) | y);
+        const uint64_t lo = pl_lower(pl, ky);
+        base[0] = uint32_t(lo);
+        len[0] = uint32_t(pl_lower(pl, ky + 1) - lo);
+      },
+      [&](uint32_t slot, uint32_t, uint32_t r) {
+        const uint32_t y = y_of(L.item[slot]);
+        const uint32_t* f = v.e3 + 3ull * pl.edge[r];
+        const uint32_t z = f[0] ^ f[1] ^ f[2] ^ c.o ^ y;
+        if (z == c.s) return;                      // an {s, o, t}
+        if (z < y && j2_near_s(v, c, z)) return;   // taken from z
+        hadd(lut, h, j2_agg_pat(v, c, y, z), 1);
+        if (has3(v.hs3, c.s, y, z)) return;        // removed at s
+        j2_remove(v, c, lut, h, y, z);
+      },
+      [](uint32_t, uint32_t) {});
+}
+
+// The 3-node hyperedges at s, entries [first, last) of its incidence row, one
+// by one (with the hyperedges at o that match one at s on the far side).
+__device__ void j2_pass_s(const View& v, const J2Ctx& c, uint32_t first, uint32_t last, uint32_t lane,
+                          uint32_t stride, const uint8_t* lut, unsigned long long* h) {
+  for (uint32_t p = v.i3_off[c.s] + first + lane; p < v.i3_off[c.s] + last; p += stride) {
+    const uint32_t* f = v.e3 + 3ull * v.i3_idx[p];
+    if (f[0] == c.o || f[1] == c.o || f[2] == c.o) continue;
+    const uint32_t y = f[0] == c.s ? f[1] : f[0], z = f[2] == c.s ? f[1] : f[2];
+    j2_remove(v, c, lut, h, y, z);
+    if (!j2_near_s(v, c, y) && !j2_near_s(v, c, z) && has3(v.hs3, c.o, y, z)) hadd(lut, h, j2_agg_pat(v, c, y, z), 1);
+  }
+}
+
+// The 4-node hyperedges holding e, entries [first, last) of the incidence row
+// of whichever of s, o has fewer of them.
+__device__ inline uint32_t j2_q_node(const View& v, const J2Ctx& c) {
+  const uint32_t fs = v.i4_off[c.s + 1] - v.i4_off[c.s], fo = v.i4_off[c.o + 1] - v.i4_off[c.o];
+  return fs <= fo ? c.s : c.o;
+}
+__device__ void j2_pass_q(const View& v, const J2Ctx& c, uint32_t first, uint32_t last, uint32_t lane,
+                          uint32_t stride, const uint8_t* lut, unsigned long long* h) {
+  const uint32_t a = j2_q_node(v, c), other = a == c.s ? c.o : c.s;
+  for (uint32_t p = v.i4_off[a] + first + lane; p < v.i4_off[a] + last; p += stride) {
+    const uint32_t* f = v.e4 + 4ull * v.i4_idx[p];
+    const uint32_t g0 = f[0], g1 = f[1], g2 = f[2], g3 = f[3];
+    if (g0 != other && g1 != other && g2 != other && g3 != other) continue;
+    uint32_t x = 0xFFFFFFFFu, y = 0xFFFFFFFFu;
+    for (const uint32_t m : {g0, g1, g2, g3}) {
+      if (m == c.s || m == c.o) continue;
+      if (x == 0xFFFFFFFFu) x = m; else y = m;
+    }
+    if (has3(v.hs3, c.s, x, y) || has3(v.hs3, c.o, x, y)) continue;   // removed with a 3-node hyperedge
+    j2_remove(v, c, lut, h, x, y);
+  }
+}
 
 __device__ void sample_j2_k4_sparse(const View& v, const PairLinks& pl, const NodeStats& ns,
-                                    const unsigned long long* __restrict__ es, const Draws& d,
+                                    const unsigned long long* __restrict__ es, const Queue& q, const Draws& d,
                                     uint32_t part, uint32_t n_parts, J2SparseLds& L, const uint8_t* lut,
                                     unsigned long long* h_lds, unsigned long long* rows) {
-  const uint32_t tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
+  const uint32_t tid = threadIdx.x;
+  __shared__ unsigned long long q_base;
   for (uint64_t smp = part; smp < d.S[2]; smp += n_parts) {
     const uint64_t i = d.at(2, smp);
     if (i >= d.n[2]) continue;
     unsigned long long* h = row_or(rows, smp, h_lds);
-    const uint32_t e0 = v.e2[2 * i], e1 = v.e2[2 * i + 1];
-    const uint32_t d0 = deg2_of(v, e0), d1 = deg2_of(v, e1);
-    const uint32_t s = d0 <= d1 ? e0 : e1, o = d0 <= d1 ? e1 : e0;
-    const uint32_t ds = d0 <= d1 ? d0 : d1, dO = d0 <= d1 ? d1 : d0;
-    const unsigned long long key = ((unsigned long long)e0 << 32) | e1;
-    const uint64_t tlo = pl.n ? pl_lower(pl, key) : 0, thi = pl.n ? pl_lower(pl, key + 1) : 0;
-    const bool any_t = thi > tlo;
-    auto in_t = [&](uint32_t y) { return any_t && has3(v.hs3, s, o, y); };
-    auto in_x = [&](uint32_t y) { return y == s || y == o || in_t(y); };
-    auto cls_of = [&](uint32_t y) { return has2(v.hs2, s, y) | (has2(v.hs2, o, y) << 1); };
-    auto t_node = [&](uint64_t p) {
-      const uint32_t* f = v.e3 + 3ull * pl.edge[p];
-      return f[0] ^ f[1] ^ f[2] ^ s ^ o;
-    };
-    auto sub = [&](uint32_t pat, unsigned long long n) {
-      const uint8_t c = lut[pat];
-      if (c != 0xFF && n) atomicAdd(&h[c], 0ull - n);
-    };
-    auto add = [&](uint32_t pat, unsigned long long n) {
-      const uint8_t c = lut[pat];
-      if (c != 0xFF && n) atomicAdd(&h[c], n);
-    };
-    if (tid < 8) L.acc[tid] = 0;
-    if (tid < 16) L.adj_tt[tid] = 0;
+    const J2Ctx c = j2_ctx(v, pl, es, d.n[2], i);
+    const uint32_t s = c.s, o = c.o, ds = c.ds, dO = c.dO;
+    const uint32_t n_t = uint32_t(c.thi - c.tlo);
     if (tid < 4) L.tcls[tid] = 0;
     __syncthreads();
-    // ---- the neighbourhood sums of e, from the per-pair statistics: with C
-    // the common neighbours, |C| = t_e; over x in C: codeg(s,x)-1, codeg(o,x)-1,
-    // |N(x) n C| (twice the 4-cliques through e) and deg x; over the other
-    // neighbours x of s: codeg(o,x)-1 = (4-cycles through e) - sum over C of (codeg(o,x)-1)
+    // class sizes of T
+    for (uint64_t p = c.tlo + tid; p < c.thi; p += kThreads) atomicAdd(&L.tcls[j2_cls(v, c, j2_t_node(v, pl, c, p))], 1u);
+    __syncthreads();
+    const uint32_t tc1 = L.tcls[1], tc2 = L.tcls[2], tc3 = L.tcls[3];
+    // ---- first term (all of A), less every pair inside T as if not joined
     if (tid == 0) {
       const uint64_t n2 = d.n[2];
       const unsigned long long te = es[i], k4 = es[n2 + i], c4 = es[2 * n2 + i];
-      const unsigned long long s_lo = es[3 * n2 + i], s_hi = es[4 * n2 + i], dsum = es[5 * n2 + i];
-      const unsigned long long ss = s == e0 ? s_lo : s_hi, so = s == e0 ? s_hi : s_lo;
-      L.acc[0] = te;
-      L.acc[1] = ss - te;
-      L.acc[2] = so - te;
-      L.acc[3] = 2 * k4;
-      L.acc[4] = dsum;
-      L.acc[5] = c4 - (so - te);
-    }
-    // class sizes of T
-    for (uint64_t p = tlo + tid; p < thi; p += kThreads) atomicAdd(&L.tcls[cls_of(t_node(p))], 1u);
-    __syncthreads();
-    const unsigned long long n3 = L.acc[0];
-    const unsigned long long na[4] = {0, ds - 1 - n3, dO - 1 - n3, n3};
-    // ---- pairs touching T.  The neighbours y of t outside e, by class,
-    // follow from |N(t) n N(s)|, |N(t) n N(s) n N(o)| (the shorter of the two
-    // rows walked) and |N(t) n N(o)| (likewise); those inside T from the
-    // shorter of N(t) and T.  Pairs with both nodes in T are taken off once,
-    // by class, at the end.
-    const uint32_t n_t = uint32_t(thi - tlo);
-    block_flat(
-        n_t, L,
-        [&](uint32_t j, uint32_t* base, uint32_t* len) {
-          const uint32_t t = t_node(tlo + j);
-          const uint32_t dt = deg2_of(v, t);
-          base[0] = dt <= ds ? v.g2_off[t] : v.g2_off[s];
-          len[0] = dt <= ds ? dt : ds;
-          base[1] = dt <= dO ? v.g2_off[t] : v.g2_off[o];
-          len[1] = dt <= dO ? dt : dO;
-          base[2] = dt <= n_t ? v.g2_off[t] : uint32_t(tlo);
-          len[2] = dt <= n_t ? dt : n_t;
-        },
-        [&](uint32_t slot, uint32_t sg, uint32_t pos) {
-          const uint32_t t = t_node(tlo + L.item[slot]);
-          const uint32_t dt = deg2_of(v, t);
-          if (sg == 0) {
-            const uint32_t z = v.g2_adj[pos];
-            const uint32_t hit = dt <= ds ? has2(v.hs2, s, z) : has2(v.hs2, t, z);
-            if (hit) {
-              atomicAdd(&L.cnt[slot][0], 1u);
-              if (has2(v.hs2, o, z)) atomicAdd(&L.cnt[slot][1], 1u);
-            }
-          } else if (sg == 1) {
-            const uint32_t z = v.g2_adj[pos];
-            if (dt <= dO ? has2(v.hs2, o, z) : has2(v.hs2, t, z)) atomicAdd(&L.cnt[slot][2], 1u);
-          } else {
-            uint32_t y;
-            if (dt <= n_t) {
-              y = v.g2_adj[pos];
-              if (y == s || y == o || !in_t(y)) return;
-            } else {
-              y = t_node(pos);
-              if (y == t || !has2(v.hs2, t, y)) return;
-            }
-            atomicAdd(&L.cnt[slot][3 + cls_of(y)], 1u);
-          }
-        },
-        [&](uint32_t slot, uint32_t j) {
-          const uint32_t t = t_node(tlo + j);
-          const uint32_t ts = has2(v.hs2, s, t), to = has2(v.hs2, o, t);
-          const uint32_t ct = ts | (to << 1);
-          const uint32_t dt = deg2_of(v, t);
-          const uint32_t a_s = L.cnt[slot][0], a_so = L.cnt[slot][1], a_o = L.cnt[slot][2];
-          const uint32_t q0 = L.cnt[slot][3], q1 = L.cnt[slot][4], q2 = L.cnt[slot][5], q3 = L.cnt[slot][6];
-          const uint32_t c3 = a_so, c1 = a_s - to - a_so, c2 = a_o - ts - a_so;
-          const uint32_t c0 = dt - ts - to - c1 - c2 - c3;
-          // neighbours outside T by class
-          const unsigned long long m0 = c0 - q0, m1 = c1 - q1, m2 = c2 - q2, m3 = c3 - q3;
-          if (ct) {
-            sub(j2_pat(ct, 1, 1), m1);
-            sub(j2_pat(ct, 2, 1), m2);
-            sub(j2_pat(ct, 3, 1), m3);
-            sub(j2_pat(ct, 0, 1), m0);
-            // pairs {t, y}, y in A outside T, not joined
-            sub(j2_pat(ct, 1, 0), na[1] - L.tcls[1] - m1);
-            sub(j2_pat(ct, 2, 0), na[2] - L.tcls[2] - m2);
-            sub(j2_pat(ct, 3, 0), na[3] - L.tcls[3] - m3);
-          } else {
-            sub(j2_pat(1, 0, 1), m1);
-            sub(j2_pat(2, 0, 1), m2);
-            sub(j2_pat(3, 0, 1), m3);
-          }
-          // joined pairs inside T, each seen from both ends
-          if (q0) atomicAdd(&L.adj_tt[ct * 4 + 0], (unsigned long long)q0);
-          if (q1) atomicAdd(&L.adj_tt[ct * 4 + 1], (unsigned long long)q1);
-          if (q2) atomicAdd(&L.adj_tt[ct * 4 + 2], (unsigned long long)q2);
-          if (q3) atomicAdd(&L.adj_tt[ct * 4 + 3], (unsigned long long)q3);
-        });
-    // ---- second term
-    auto remove = [&](uint32_t x, uint32_t y) {
-      if (in_x(x) || in_x(y)) return;
-      sub(1u | (has2(v.hs2, s, x) << 1) | (has2(v.hs2, o, x) << 2) | (has2(v.hs2, s, y) << 4) |
-              (has2(v.hs2, o, y) << 5) | (has2(v.hs2, x, y) << 7),
-          1);
-    };
-    // a 3-node hyperedge {o, y, z} as the histogram at o counts it
-    auto agg_pat = [&](uint32_t y, uint32_t z) {
-      if (z < y) {
-        const uint32_t t = y;
-        y = z;
-        z = t;
-      }
-      return 1u | (has2(v.hs2, o, y) << 2) | (has2(v.hs2, o, z) << 5) | (has2(v.hs2, y, z) << 7);
-    };
-    auto near_s = [&](uint32_t y) { return has2(v.hs2, s, y) || in_t(y); };
-    // at s, one by one (and the hyperedges at o that match one at s on the far side)
-    for (uint32_t p = v.i3_off[s] + tid; p < v.i3_off[s + 1]; p += kThreads) {
-      const uint32_t* f = v.e3 + 3ull * v.i3_idx[p];
-      if (f[0] == o || f[1] == o || f[2] == o) continue;
-      const uint32_t y = f[0] == s ? f[1] : f[0], z = f[2] == s ? f[1] : f[2];
-      remove(y, z);
-      if (!near_s(y) && !near_s(z) && has3(v.hs3, o, y, z)) add(agg_pat(y, z), 1);
-    }
-    // at o, from its histogram
-    if (tid < 8) {
-      const uint32_t b = tid;
-      sub(1u | ((b & 1u) << 2) | (((b >> 1) & 1u) << 5) | ((b >> 2) << 7), ns.h3[8ull * o + b]);
-    }
-    // corrections: the hyperedges {s, o, t}
-    for (uint64_t p = tlo + tid; p < thi; p += kThreads) add(agg_pat(s, t_node(p)), 1);
-    // corrections: {o, y, z} with y in N(s) u T (taken from the smaller of y, z when both are)
-    {
-      const uint32_t sb = v.g2_off[s];
-      auto y_of = [&](uint32_t j) { return j < ds ? v.g2_adj[sb + j] : t_node(tlo + (j - ds)); };
-      block_flat(
-          ds + n_t, L,
-          [&](uint32_t j, uint32_t* base, uint32_t* len) {
-            const uint32_t y = y_of(j);
-            if (y == o || (j >= ds && has2(v.hs2, s, y))) return;   // o, or a node of T taken as a neighbour of s
-            const unsigned long long ky =
-                y < o ? (((unsigned long long)y << 32) | o) : (((unsigned long long)o << 32) | y);
-            const uint64_t lo = pl_lower(pl, ky);
-            base[0] = uint32_t(lo);
-            len[0] = uint32_t(pl_lower(pl, ky + 1) - lo);
-          },
-          [&](uint32_t slot, uint32_t, uint32_t r) {
-            const uint32_t y = y_of(L.item[slot]);
-            const uint32_t* f = v.e3 + 3ull * pl.edge[r];
-            const uint32_t z = f[0] ^ f[1] ^ f[2] ^ o ^ y;
-            if (z == s) return;                 // an {s, o, t}
-            if (z < y && near_s(z)) return;     // taken from z
-            add(agg_pat(y, z), 1);
-            if (has3(v.hs3, s, y, z)) return;   // removed at s
-            remove(y, z);
-          },
-          [](uint32_t, uint32_t) {});
-    }
-    // 4-node hyperedges holding e
-    {
-      const uint32_t fs = v.i4_off[s + 1] - v.i4_off[s], fo = v.i4_off[o + 1] - v.i4_off[o];
-      const uint32_t a = fs <= fo ? s : o, other = fs <= fo ? o : s;
-      for (uint32_t p = v.i4_off[a] + tid; p < v.i4_off[a + 1]; p += kThreads) {
-        const uint32_t* f = v.e4 + 4ull * v.i4_idx[p];
-        const uint32_t g0 = f[0], g1 = f[1], g2 = f[2], g3 = f[3];
-        if (g0 != other && g1 != other && g2 != other && g3 != other) continue;
-        uint32_t x = 0xFFFFFFFFu, y = 0xFFFFFFFFu;
-        for (const uint32_t m : {g0, g1, g2, g3}) {
-          if (m == s || m == o) continue;
-          if (x == 0xFFFFFFFFu) x = m; else y = m;
-        }
-        if (has3(v.hs3, s, x, y) || has3(v.hs3, o, x, y)) continue;   // removed with a 3-node hyperedge
-        remove(x, y);
-      }
-    }
-    __syncthreads();
-    // ---- first term (all of A), and the pairs inside T not joined
-    if (tid == 0) {
-      const unsigned long long cs = L.acc[1], co = L.acc[2], cc = L.acc[3], d3 = L.acc[4], c1o = L.acc[5];
+      const unsigned long long s_lo = es[3 * n2 + i], s_hi = es[4 * n2 + i], d3 = es[5 * n2 + i];
+      const unsigned long long ss = s == c.e0 ? s_lo : s_hi, so = s == c.e0 ? s_hi : s_lo;
+      // over the common neighbours x: codeg(s,x)-1, codeg(o,x)-1, |N(x) n A_3|;
+      // over the other neighbours x of s: codeg(o,x)-1
+      const unsigned long long cs = ss - te, co = so - te, cc = 2 * k4, c1o = c4 - co;
       const unsigned long long e33 = cc / 2, e13 = cs - cc, e23 = co - cc;
-      const unsigned long long e11 = (ns.tri[s] - n3) - e13 - e33;
-      const unsigned long long e22 = (ns.tri[o] - n3) - e23 - e33;
+      const unsigned long long e11 = (ns.tri[s] - te) - e13 - e33;
+      const unsigned long long e22 = (ns.tri[o] - te) - e23 - e33;
       const unsigned long long e12 = c1o - e13;
       const unsigned long long dsum[4] = {0, ns.nbr[s] - dO - d3, ns.nbr[o] - ds - d3, d3};
       const unsigned long long e[4][4] = {{0, 0, 0, 0}, {0, e11, e12, e13}, {0, e12, e22, e23}, {0, e13, e23, e33}};
+      const unsigned long long tcl[4] = {0, tc1, tc2, tc3};
+#pragma unroll
       for (uint32_t p = 1; p <= 3; ++p) {
-        for (uint32_t q = p; q <= 3; ++q) {
-          const unsigned long long tot = p == q ? na[p] * (na[p] - (na[p] > 0)) / 2 : na[p] * na[q];
-          add(j2_pat(p, q, 1), e[p][q]);
-          add(j2_pat(p, q, 0), tot - e[p][q]);
-          // pairs inside T in these classes: joined (seen twice) and not joined
-          const unsigned long long tp = L.tcls[p], tq = L.tcls[q];
-          const unsigned long long ttot = p == q ? tp * (tp - (tp > 0)) / 2 : tp * tq;
-          const unsigned long long tadj = p == q ? L.adj_tt[p * 4 + p] / 2 : L.adj_tt[p * 4 + q];
-          sub(j2_pat(p, q, 1), tadj);
-          sub(j2_pat(p, q, 0), ttot - tadj);
+#pragma unroll
+        for (uint32_t r = p; r <= 3; ++r) {
+          const unsigned long long tot = p == r ? c.na[p] * (c.na[p] - (c.na[p] > 0)) / 2 : c.na[p] * c.na[r];
+          hadd(lut, h, j2_pat(p, r, 1), e[p][r]);
+          hadd(lut, h, j2_pat(p, r, 0), tot - e[p][r]);
+          const unsigned long long tp = tcl[p], tr = tcl[r];
+          hsub(lut, h, j2_pat(p, r, 0), p == r ? tp * (tp - (tp > 0)) / 2 : tp * tr);
         }
-        // joined pairs inside T with one node outside A: it hangs off the other
-        sub(j2_pat(p, 0, 1), L.adj_tt[p * 4 + 0]);
         const unsigned long long inside = 2 * e[p][p] + e[p][1] + e[p][2] + e[p][3] - e[p][p];
-        add(j2_pat(p, 0, 1), dsum[p] - na[p] * (p == 3 ? 2 : 1) - inside);
+        hadd(lut, h, j2_pat(p, 0, 1), dsum[p] - c.na[p] * (p == 3 ? 2 : 1) - inside);
       }
+    }
+    // ---- second term
+    // at o, from its histogram
+    if (tid < 8) {
+      const uint32_t bb = tid;
+      hsub(lut, h, 1u | ((bb & 1u) << 2) | (((bb >> 1) & 1u) << 5) | ((bb >> 2) << 7), ns.h3[8ull * o + bb]);
+    }
+    // corrections: the hyperedges {s, o, t}
+    for (uint64_t p = c.tlo + tid; p < c.thi; p += kThreads) hadd(lut, h, j2_agg_pat(v, c, s, j2_t_node(v, pl, c, p)), 1);
+    // ---- the walks over T and over the corrections, and the hyperedges at s
+    // and holding e: here when short, else queued
+    const uint32_t n_r = ds + n_t;
+    const uint32_t n_s = v.i3_off[s + 1] - v.i3_off[s];
+    const uint32_t qn = j2_q_node(v, c), n_q = v.i4_off[qn + 1] - v.i4_off[qn];
+    const uint32_t jobs_t = (n_t + kChunkT - 1) / kChunkT, jobs_r = (n_r + kChunkR - 1) / kChunkR;
+    const uint32_t jobs_s = (n_s + kChunkH - 1) / kChunkH, jobs_q = (n_q + kChunkH - 1) / kChunkH;
+    const uint32_t jobs = jobs_t + jobs_r + jobs_s + jobs_q;
+    bool here = q.job == nullptr || (jobs_t <= 1 && jobs_r <= 1 && jobs_s <= 1 && jobs_q <= 1);
+    if (!here) {
+      if (tid == 0) {
+        q_base = queue_reserve(q, jobs);
+        if (q_base != ~0ull) {
+          q.tcls[3 * smp] = tc1;
+          q.tcls[3 * smp + 1] = tc2;
+          q.tcls[3 * smp + 2] = tc3;
+        }
+      }
+      __syncthreads();
+      here = q_base == ~0ull;
+      if (!here) {
+        for (uint32_t k = tid; k < jobs; k += kThreads) {
+          uint32_t kind, first, last;
+          if (k < jobs_t) {
+            kind = kJobPairT;
+            first = k * kChunkT;
+            last = min(first + kChunkT, n_t);
+          } else if (k < jobs_t + jobs_r) {
+            kind = kJobPairR;
+            first = (k - jobs_t) * kChunkR;
+            last = min(first + kChunkR, n_r);
+          } else if (k < jobs_t + jobs_r + jobs_s) {
+            kind = kJobPairS;
+            first = (k - jobs_t - jobs_r) * kChunkH;
+            last = min(first + kChunkH, n_s);
+          } else {
+            kind = kJobPairQ;
+            first = (k - jobs_t - jobs_r - jobs_s) * kChunkH;
+            last = min(first + kChunkH, n_q);
+          }
+          q.job[q_base + k] = make_uint4(kind, uint32_t(smp), first, last);
+        }
+      }
+    }
+    if (here) {
+      j2_pass_s(v, c, 0, n_s, tid, kThreads, lut, h);
+      j2_pass_q(v, c, 0, n_q, tid, kThreads, lut, h);
+      j2_walk_t(v, pl, c, tc1, tc2, tc3, 0, n_t, L, lut, h);
+      j2_walk_r(v, pl, c, 0, n_r, L, lut, h);
     }
     __syncthreads();
   }
@@ -636,6 +798,7 @@ struct SampledArgs {
   PairLinks pl;                  // pair -> 3-node hyperedge index (no bit rows)
   NodeStats ns;                  // per-node statistics (no bit rows)
   const unsigned long long* es;  // per-pair statistics (no bit rows)
+  Queue q;                       // work queue (no bit rows; q.job == null otherwise)
   Draws d;
   const uint8_t* lut;
   uint32_t blocks[5];            // workgroups of strata 2, 3, 4 (in this order in the grid)
@@ -663,6 +826,37 @@ struct SampledLds<4, false> {
   J2SparseLds j2;
 };
 
+// After a workgroup's counts reached a.hist: the last workgroup of the launch
+// scales them (Algorithm 4's correction: est_m = raw_m * |E_mc| / (S_mc *
+// countmax_m) in fp64, rounded once to fp32, 0 when the stratum was not
+// sampled) and clears a.hist, the ticket and the queue counters.
+__device__ void finish_sampled(const SampledArgs& a, const ScaleArgs& sc) {
+  __shared__ uint32_t last;
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) last = atomicAdd(a.ticket, 1u) == gridDim.x - 1;
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  const int c = threadIdx.x;
+  const unsigned long long r = __hip_atomic_load(a.hist + c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (a.est && c < a.n_classes) {
+    const int j = sc.maxcard[c];
+    double e = 0.0;
+    if (sc.s_by_size[j] > 0.0) e = (double(r) * sc.n_by_size[j]) / (sc.s_by_size[j] * double(sc.countmax[c]));
+    a.est[c] = float(e);
+    if (a.raw) a.raw[c] = int64_t(r);
+  }
+  a.hist[c] = 0;
+  if (c == 0) {
+    *a.ticket = 0;
+    if (a.q.job) {
+      *a.q.tail = 0;
+      *a.q.head = 0;
+    }
+  }
+}
+
 // Every stratum's samples in one launch.  The grid holds a.blocks[2]
 // workgroups for the sampled pairs, then a.blocks[3] for the 3-node and
 // a.blocks[4] for the 4-node hyperedges.  Each workgroup adds its LDS counts to
@@ -675,7 +869,6 @@ __global__ void __launch_bounds__(kThreads) k_sampled(SampledArgs a, ScaleArgs s
   __shared__ uint8_t lut[kLut];
   __shared__ unsigned long long h_lds[256];
   __shared__ SampledLds<K, BITS> lds;
-  __shared__ uint32_t last;
   load_lut(lut, a.lut, kLut);
   h_lds[threadIdx.x] = 0;
   __syncthreads();
@@ -684,14 +877,14 @@ __global__ void __launch_bounds__(kThreads) k_sampled(SampledArgs a, ScaleArgs s
     if constexpr (K == 4 && BITS)
       sample_j2_k4_bits(a.v, a.d, b, a.blocks[2], lds.j2, lut, h_lds, a.rows[2]);
     else if constexpr (K == 4)
-      sample_j2_k4_sparse(a.v, a.pl, a.ns, a.es, a.d, b, a.blocks[2], lds.j2, lut, h_lds, a.rows[2]);
+      sample_j2_k4_sparse(a.v, a.pl, a.ns, a.es, a.q, a.d, b, a.blocks[2], lds.j2, lut, h_lds, a.rows[2]);
     else
       sample_j2_k3(a.v, a.d, b, a.blocks[2], lut, h_lds, a.rows[2]);
   } else if ((b -= a.blocks[2]) < a.blocks[3]) {
     if constexpr (K == 4 && BITS)
-      sample_j3_k4<true>(a.v, a.pl, a.d, b, a.blocks[3], lds.b4, lut, h_lds, a.rows[3]);
+      sample_j3_k4<true>(a.v, a.pl, a.q, a.d, b, a.blocks[3], lds.b4, lut, h_lds, a.rows[3]);
     else if constexpr (K == 4)
-      sample_j3_k4<false>(a.v, a.pl, a.d, b, a.blocks[3], nullptr, lut, h_lds, a.rows[3]);
+      sample_j3_k4<false>(a.v, a.pl, a.q, a.d, b, a.blocks[3], nullptr, lut, h_lds, a.rows[3]);
     else
       sample_j3_k3(a.v, a.d, b, a.blocks[3], lut, h_lds, a.rows[3]);
   } else if (K == 4) {
@@ -700,24 +893,55 @@ __global__ void __launch_bounds__(kThreads) k_sampled(SampledArgs a, ScaleArgs s
   }
   __syncthreads();
   flush(h_lds, a.hist, 256);
-  if (!a.est) return;
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) last = atomicAdd(a.ticket, 1u) == gridDim.x - 1;
-  __syncthreads();
-  if (!last) return;
-  __threadfence();
-  const int c = threadIdx.x;
-  const unsigned long long r = __hip_atomic_load(a.hist + c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  if (c < a.n_classes) {
-    const int j = sc.maxcard[c];
-    double e = 0.0;
-    if (sc.s_by_size[j] > 0.0) e = (double(r) * sc.n_by_size[j]) / (sc.s_by_size[j] * double(sc.countmax[c]));
-    a.est[c] = float(e);
-    if (a.raw) a.raw[c] = int64_t(r);
+  if (a.q.job) return;   // the queue's drain finishes the call
+  finish_sampled(a, sc);
+}
+
+// Drain the work queue that k_sampled filled (without bit rows), then finish
+// the call as k_sampled does otherwise.
+__global__ void __launch_bounds__(kThreads) k_sampled_drain(SampledArgs a, ScaleArgs sc) {
+  __shared__ uint8_t lut[2048];
+  __shared__ unsigned long long h_lds[256];
+  __shared__ J2SparseLds L;
+  __shared__ uint4 job;
+  __shared__ uint32_t tcls[3];
+  load_lut(lut, a.lut, 2048);
+  h_lds[threadIdx.x] = 0;
+  const unsigned long long n_jobs = min(__hip_atomic_load(a.q.tail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT), a.q.cap);
+  for (;;) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const unsigned long long k = atomicAdd(a.q.head, 1ull);
+      job = k < n_jobs ? a.q.job[k] : make_uint4(0xFFFFFFFFu, 0, 0, 0);
+    }
+    __syncthreads();
+    const uint4 jb = job;
+    if (jb.x == 0xFFFFFFFFu) break;
+    if (jb.x == kJobPairS || jb.x == kJobPairQ) {
+      const J2Ctx c = j2_ctx(a.v, a.pl, a.es, a.d.n[2], a.d.at(2, jb.y));
+      unsigned long long* h = row_or(a.rows[2], jb.y, h_lds);
+      if (jb.x == kJobPairS) j2_pass_s(a.v, c, jb.z, jb.w, threadIdx.x, kThreads, lut, h);
+      else j2_pass_q(a.v, c, jb.z, jb.w, threadIdx.x, kThreads, lut, h);
+    } else if (jb.x == kJobPairT || jb.x == kJobPairR) {
+      const uint64_t i = a.d.at(2, jb.y);
+      const J2Ctx c = j2_ctx(a.v, a.pl, a.es, a.d.n[2], i);
+      unsigned long long* h = row_or(a.rows[2], jb.y, h_lds);
+      if (jb.x == kJobPairT) {
+        if (threadIdx.x < 3) tcls[threadIdx.x] = a.q.tcls[3ull * jb.y + threadIdx.x];
+        __syncthreads();
+        j2_walk_t(a.v, a.pl, c, tcls[0], tcls[1], tcls[2], jb.z, jb.w, L, lut, h);
+      } else {
+        j2_walk_r(a.v, a.pl, c, jb.z, jb.w, L, lut, h);
+      }
+    } else if (jb.x == kJobTriple) {
+      const uint64_t i = a.d.at(3, jb.y);
+      const B4Ctx x = b4_ctx(a.v, a.pl, a.v.e3[3 * i], a.v.e3[3 * i + 1], a.v.e3[3 * i + 2]);
+      j3_exceptions(a.v, a.pl, x, jb.z, jb.w, threadIdx.x, kThreads, lut, row_or(a.rows[3], jb.y, h_lds));
+    }
   }
-  a.hist[c] = 0;
-  if (c == 0) *a.ticket = 0;
+  __syncthreads();
+  flush(h_lds, a.hist, 256);
+  finish_sampled(a, sc);
 }
 
 unsigned grid_for(uint64_t items, uint64_t per_block, unsigned cap = 512) {
@@ -797,6 +1021,28 @@ int launch_sampled(const hm_graph* H, int k, const uint32_t* const idx[5], const
     sc.maxcard[c] = c < t.n_classes[k] ? t.maxcard[k][c] : 0;
     sc.countmax[c] = c < t.n_classes[k] ? t.countmax[k][c] : 1;
   }
+  // work queue of heavy samples (order 4 without bit rows); its buffers stay
+  // with the caching allocator, which hands them out again only to work
+  // enqueued after this call
+  a.q.job = nullptr;
+  a.q.cap = 0;
+  a.q.tail = H->sample_hist + 257;
+  a.q.head = H->sample_hist + 258;
+  a.q.tcls = nullptr;
+  struct Release {
+    void* p[2] = {nullptr, nullptr};
+    ~Release() {
+      dfree(p[0]);
+      dfree(p[1]);
+    }
+  } rel;
+  if (k == 4 && !bits) {
+    a.q.cap = 32ull * (a.d.S[2] + a.d.S[3]) + 65536;
+    HM_TRY(dalloc(&rel.p[0], a.q.cap * sizeof(uint4)));
+    HM_TRY(dalloc(&rel.p[1], (3 * a.d.S[2] + 1) * sizeof(uint32_t)));
+    a.q.job = static_cast<uint4*>(rel.p[0]);
+    a.q.tcls = static_cast<uint32_t*>(rel.p[1]);
+  }
   ProfileScope pscope("k_sampled", st);
   if (k == 4 && bits)
     k_sampled<4, true><<<grid, kThreads, 0, st>>>(a, sc);
@@ -805,6 +1051,10 @@ int launch_sampled(const hm_graph* H, int k, const uint32_t* const idx[5], const
   else
     k_sampled<3, false><<<grid, kThreads, 0, st>>>(a, sc);
   HM_HIP(hipGetLastError());
+  if (a.q.job) {
+    k_sampled_drain<<<1024, kThreads, 0, st>>>(a, sc);
+    HM_HIP(hipGetLastError());
+  }
   return HM_OK;
 }
 

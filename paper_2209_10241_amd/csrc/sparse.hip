@@ -170,12 +170,11 @@ __global__ void __launch_bounds__(kThreads) k_sp_c4(View v, uint32_t* __restrict
   block_add(total, acc + kAccC4);
 }
 
-// Neighbours that follow each node in degree order.
-__global__ void k_sp_outdeg(View v, uint32_t* __restrict__ outdeg) {
-  for (uint32_t x = blockIdx.x * blockDim.x + threadIdx.x; x < v.N; x += gridDim.x * blockDim.x) {
-    uint32_t n = 0;
-    for (uint32_t p = v.g2_off[x]; p < v.g2_off[x + 1]; ++p) n += rank_less(v, x, v.g2_adj[p]);
-    outdeg[x] = n;
+// Neighbours that follow each node in degree order (outdeg zeroed by the caller).
+__global__ void k_sp_outdeg(View v, uint64_t n2, uint32_t* __restrict__ outdeg) {
+  for (uint64_t e = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < n2; e += uint64_t(gridDim.x) * blockDim.x) {
+    const uint32_t a = v.e2[2 * e], b = v.e2[2 * e + 1];
+    atomicAdd(&outdeg[rank_less(v, a, b) ? a : b], 1u);
   }
 }
 
@@ -476,7 +475,8 @@ int ensure_edge_stats(hm_graph* H, hipStream_t st) {
       k_es_sums<<<grid_cap(n2, kWavesPerBlock, 2048), kThreads, 0, st>>>(v, n2, H->g2_eid, tri_e, es + 3 * n2,
                                                                          es + 4 * n2, es + 5 * n2);
       k_sp_c4<true><<<g, kThreads, 0, st>>>(v, cnt, touched, acc, H->g2_eid, es + 2 * n2);
-      k_sp_outdeg<<<grid_cap(N, 256, 1024), 256, 0, st>>>(v, outdeg);
+      if (fill_u32(outdeg, 0, N, st) != HM_OK) rc = HM_EDEVICE;
+      k_sp_outdeg<<<grid_cap(n2, 256, 2048), 256, 0, st>>>(v, n2, outdeg);
       if (hipGetLastError() != hipSuccess) rc = HM_EDEVICE;
       if (rc == HM_OK) rc = max_u32(outdeg, N, dmax, st);
       uint32_t cap = 0;
@@ -593,7 +593,8 @@ int count_sparse(const hm_graph* H, int k, hipStream_t st) {
     HM_TRY(tmp.get(&outdeg, H->n_nodes));
     HM_TRY(tmp.get(&dmax, 1));
     HM_TRY(fill_u32(dmax, 0, 1, st));
-    k_sp_outdeg<<<grid_cap(H->n_nodes, 256, 1024), 256, 0, st>>>(v, outdeg);
+    HM_TRY(fill_u32(outdeg, 0, H->n_nodes, st));
+    k_sp_outdeg<<<grid_cap(n2, 256, 2048), 256, 0, st>>>(v, n2, outdeg);
     HM_TRY(max_u32(outdeg, H->n_nodes, dmax, st));
     uint32_t cap = 0;
     HM_HIP(hipMemcpyAsync(&cap, dmax, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
