@@ -83,6 +83,87 @@ def measured_traffic() -> dict:
     return out
 
 
+def _mre(runs, exact) -> float:
+    r = np.asarray(runs, dtype=np.float64)
+    return float(np.mean(np.abs(r - exact).sum(axis=1) / exact.sum()))
+
+
+def large_workloads(hm, W, torch, seeds: int = 32) -> dict:
+    """Exact order-4 counts and sampled estimates (uniform, and the learned
+    proposal trained on a 5% hyperedge subsample) on the heavy-tailed workloads."""
+    out = {}
+    stream = torch.cuda.current_stream()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def timed(fn, reps):
+        ev0.record(stream)
+        res = [fn(i) for i in range(reps)]
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        return ev0.elapsed_time(ev1) / reps, res
+
+    for name, maker in (("coauthorship_N1e6_E2e6", W.cfg3_coauthorship), ("communication_N5e4_E5e6", W.cfg4_communication)):
+        h = maker(0)
+        dev = torch.device("cuda:0")
+        members = torch.from_numpy(h.members.astype(np.int32)).to(dev)
+        offsets = torch.from_numpy(h.offsets.astype(np.int64)).to(dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g = hm.hm_graph_create(members, offsets, h.n_nodes, stream=stream)
+        torch.cuda.synchronize()
+        ingest_ms = (time.perf_counter() - t0) * 1e3
+        st = g.stats()
+        hm.count_exact(g, 4, stream=stream)
+        exact_ms, res = timed(lambda i: hm.count_exact(g, 4, stream=stream), 3)
+        exact = res[-1].cpu().numpy().astype(np.float64)
+        h5 = W.subsample_edges(h, 0.05, seed=3)
+        g5 = hm.hm_graph_create(h5.members, h5.offsets, h5.n_nodes, stream=stream)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        model = hm.hm_model_train(g5, 4, epochs=30, batch=4096, lr=3e-3, seed=2)
+        torch.cuda.synchronize()
+        train_ms = (time.perf_counter() - t0) * 1e3
+        t0 = time.perf_counter()
+        hm.count_sampled(g, 4, 0.01, 7, stream=stream)
+        torch.cuda.synchronize()
+        first_uniform_ms = (time.perf_counter() - t0) * 1e3
+        t0 = time.perf_counter()
+        hm.count_sampled_learned(g, model, 4, 0.01, 7, stream=stream)
+        torch.cuda.synchronize()
+        first_learned_ms = (time.perf_counter() - t0) * 1e3
+        rows = {}
+        for f in (0.0025, 0.005, 0.01, 0.02):
+            ms_u, ru = timed(lambda i: hm.count_sampled(g, 4, f, 1000 + i, stream=stream)[0], seeds)
+            ms_l, rl = timed(lambda i: hm.count_sampled_learned(g, model, 4, f, 1000 + i, stream=stream)[0], seeds)
+            rows[f"{f:g}"] = {
+                "uniform": {"ms": ms_u, "mre": _mre(torch.stack(ru).cpu().numpy(), exact), "speedup_vs_exact": exact_ms / ms_u},
+                "learned": {"ms": ms_l, "mre": _mre(torch.stack(rl).cpu().numpy(), exact), "speedup_vs_exact": exact_ms / ms_l},
+            }
+
+        def best(kind):
+            ok = [(v[kind]["ms"], k) for k, v in rows.items() if v[kind]["mre"] <= 0.02]
+            if not ok:
+                return None
+            ms, k = min(ok)
+            return {"fraction": float(k), "ms": ms, "mre": rows[k][kind]["mre"], "speedup_vs_exact": exact_ms / ms}
+
+        out[name] = {
+            "n_nodes": h.n_nodes, "unique_by_size": [st["n2"], st["n3"], st["n4"], st["n5plus"]],
+            "connected_4_sets": int(exact.sum()), "ingest_ms": ingest_ms, "exact_ms": exact_ms,
+            "first_call_ms": {"uniform_1pct_incl_index_build": first_uniform_ms,
+                              "learned_1pct_incl_proposal": first_learned_ms},
+            "learned_training_ms": train_ms, "training_set": "5% hyperedge subsample",
+            "sampled": rows, "fastest_at_2pct_mre": {"uniform": best("uniform"), "learned": best("learned")},
+            "seeds": seeds,
+        }
+        model.close()
+        g5.close()
+        g.close()
+        del members, offsets
+        torch.cuda.empty_cache()
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -90,6 +171,8 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--exact-only", action="store_true", help="skip the sampled and null-model measurements")
+    ap.add_argument("--no-large", action="store_true",
+                    help="skip the co-authorship and communication workloads (exact, uniform and learned sampling)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first copy 256 MiB device to device (a kernel of known traffic for counter scaling)")
     args = ap.parse_args()
@@ -208,6 +291,8 @@ def main() -> int:
                 "frac": byts / avg_s / 1e9 / HBM_PEAK_GBS, "traffic": traffic.get("k_case_b4")}
     roof["kernel"] = dom
 
+    large = None if (args.no_large or args.exact_only) else large_workloads(hm, W, torch)
+
     cpu = None
     if not args.no_cpu_baseline:
         from oracle import core
@@ -241,6 +326,7 @@ def main() -> int:
         "sampled_speedup_at_2pct": ({"fraction": float(best), "speedup": sampled[best]["speedup_vs_exact_count"]}
                                     if best else None),
         "nulls": nulls,
+        "large_workloads": large,
         "kernels": kernels,
         "units": units,
         "roofline": roof,
