@@ -278,8 +278,17 @@ int count_sampled_weighted_indices(const hm_graph* H, int k, const uint32_t* idx
  *                            the counting kernels use for pair tests and
  *                            neighbour intersections; 0 forces the hash-set
  *                            probes everywhere.
+ *   HM_OPT_SAMPLE_CHUNK_SCALE the sampled counts of graphs without bit rows
+ *                            hand the long walks of heavy samples to a work
+ *                            queue in chunks (64 nodes of T, 256 correction
+ *                            items, 512 exception positions, 1024 hyperedges);
+ *                            every chunk size is divided by this value
+ *                            (default 1, range 1..1024), so larger values
+ *                            route more of the work through the queue.  The
+ *                            results do not depend on it.
  * HM_EINVAL for an unknown option or a value out of range. */
 #define HM_OPT_BITSET_MAX_NODES 1
+#define HM_OPT_SAMPLE_CHUNK_SCALE 2
 int hm_set_option(int option, int64_t value);
 int hm_get_option(int option, int64_t* value);
 

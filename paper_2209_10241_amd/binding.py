@@ -24,6 +24,7 @@ HM_EINTERNAL = -5
 HM_MEM_HOST = 0
 HM_MEM_DEVICE = 1
 HM_OPT_BITSET_MAX_NODES = 1
+HM_OPT_SAMPLE_CHUNK_SCALE = 2
 HM_ALLOC_PROPORTIONAL = 0
 HM_ALLOC_PAPER = 1
 

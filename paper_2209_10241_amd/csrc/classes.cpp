@@ -137,6 +137,8 @@ void set_error(const char* fmt, ...) {
 const char* last_error() { return g_err; }
 
 uint32_t bitset_max_nodes() { return g_bitset_max_nodes.load(); }
+std::atomic<uint32_t> g_sample_chunk_scale{1};
+uint32_t sample_chunk_scale() { return g_sample_chunk_scale.load(); }
 
 const ClassTables& class_tables() {
   static const ClassTables t = build();
@@ -252,6 +254,14 @@ int hm_set_option(int option, int64_t value) {
     hm::g_bitset_max_nodes.store(uint32_t(value));
     return HM_OK;
   }
+  if (option == HM_OPT_SAMPLE_CHUNK_SCALE) {
+    if (value < 1 || value > 1024) {
+      hm::set_error("HM_OPT_SAMPLE_CHUNK_SCALE must be in [1, 1024]");
+      return HM_EINVAL;
+    }
+    hm::g_sample_chunk_scale.store(uint32_t(value));
+    return HM_OK;
+  }
   hm::set_error("unknown option %d", option);
   return HM_EINVAL;
 }
@@ -263,6 +273,10 @@ int hm_get_option(int option, int64_t* value) {
   }
   if (option == HM_OPT_BITSET_MAX_NODES) {
     *value = hm::g_bitset_max_nodes.load();
+    return HM_OK;
+  }
+  if (option == HM_OPT_SAMPLE_CHUNK_SCALE) {
+    *value = hm::g_sample_chunk_scale.load();
     return HM_OK;
   }
   hm::set_error("unknown option %d", option);

@@ -22,6 +22,7 @@ constexpr unsigned long long kEmpty64 = ~0ull;
 // largest value HM_OPT_BITSET_MAX_NODES accepts)
 constexpr uint32_t kBitsetMaxNodes = 8192;
 uint32_t bitset_max_nodes();
+uint32_t sample_chunk_scale();
 
 // ----------------------------------------------------------------- errors
 void set_error(const char* fmt, ...);

@@ -8,6 +8,7 @@
 // sub-hypergraph holds no hyperedge larger than e adds one to its class (raw
 // counts).  The estimate of class m is raw_m * |E_mc| / (S_mc * countmax_m)
 // with mc = maxcard(m), formed in fp64 and rounded once to fp32.
+#include <algorithm>
 #include <cmath>
 
 #include "hm_sparse.h"
@@ -74,6 +75,7 @@ __device__ void sample_j4(const View& v, const Draws& d, uint32_t part, uint32_t
 // Work chunks of heavy samples (without bit rows), drained by every
 // workgroup of a second launch so that one sample's work spreads over many.
 enum : uint32_t { kJobNone = 0, kJobPairT = 1, kJobPairR = 2, kJobTriple = 3, kJobPairS = 4, kJobPairQ = 5 };
+// default chunk sizes (divided by the HM_OPT_SAMPLE_CHUNK_SCALE option)
 constexpr uint32_t kChunkT = 64;    // nodes of T per chunk
 constexpr uint32_t kChunkR = 256;   // correction items per chunk
 constexpr uint32_t kChunkX = 512;   // exception positions per chunk
@@ -85,6 +87,7 @@ struct Queue {
   unsigned long long* tail;     // reserved entries (may pass cap: those are done in place)
   unsigned long long* head;     // claimed entries
   uint32_t* tcls;               // per pair sample: |T n A_q|, q = 1..3
+  uint32_t ct, cr, cx, ch;      // chunk sizes: nodes of T, correction items, exception positions, hyperedges
 };
 
 // Reserve n entries; returns the first, or ~0 when they do not fit (the
@@ -138,7 +141,7 @@ __device__ void sample_j3_k4(const View& v, const PairLinks& pl, const Queue& q,
         for (uint32_t cmb = 1; cmb < 8; ++cmb)
           if (n[cmb]) atomicAdd(&h[lut[b4_combo_pattern(x, cmb)]], (unsigned long long)n[cmb]);
       }
-      const uint64_t jobs = (x.total + kChunkX - 1) / kChunkX;
+      const uint64_t jobs = (x.total + q.cx - 1) / q.cx;
       unsigned long long base = ~0ull;
       if (q.job && jobs > 1) {
         if (lane == 0) base = queue_reserve(q, uint32_t(jobs));
@@ -148,8 +151,8 @@ __device__ void sample_j3_k4(const View& v, const PairLinks& pl, const Queue& q,
         j3_exceptions(v, pl, x, 0, x.total, lane, kWave, lut, h);
       } else {
         for (uint64_t k = lane; k < jobs; k += kWave)
-          q.job[base + k] = make_uint4(kJobTriple, uint32_t(s), uint32_t(k * kChunkX),
-                                       uint32_t(min<uint64_t>((k + 1) * kChunkX, x.total)));
+          q.job[base + k] = make_uint4(kJobTriple, uint32_t(s), uint32_t(k * q.cx),
+                                       uint32_t(min<uint64_t>((k + 1) * q.cx, x.total)));
       }
     }
   }
@@ -532,8 +535,8 @@ __device__ void sample_j2_k4_sparse(const View& v, const PairLinks& pl, const No
     const uint32_t n_r = ds + n_t;
     const uint32_t n_s = v.i3_off[s + 1] - v.i3_off[s];
     const uint32_t qn = j2_q_node(v, c), n_q = v.i4_off[qn + 1] - v.i4_off[qn];
-    const uint32_t jobs_t = (n_t + kChunkT - 1) / kChunkT, jobs_r = (n_r + kChunkR - 1) / kChunkR;
-    const uint32_t jobs_s = (n_s + kChunkH - 1) / kChunkH, jobs_q = (n_q + kChunkH - 1) / kChunkH;
+    const uint32_t jobs_t = (n_t + q.ct - 1) / q.ct, jobs_r = (n_r + q.cr - 1) / q.cr;
+    const uint32_t jobs_s = (n_s + q.ch - 1) / q.ch, jobs_q = (n_q + q.ch - 1) / q.ch;
     const uint32_t jobs = jobs_t + jobs_r + jobs_s + jobs_q;
     bool here = q.job == nullptr || (jobs_t <= 1 && jobs_r <= 1 && jobs_s <= 1 && jobs_q <= 1);
     if (!here) {
@@ -552,20 +555,20 @@ __device__ void sample_j2_k4_sparse(const View& v, const PairLinks& pl, const No
           uint32_t kind, first, last;
           if (k < jobs_t) {
             kind = kJobPairT;
-            first = k * kChunkT;
-            last = min(first + kChunkT, n_t);
+            first = k * q.ct;
+            last = min(first + q.ct, n_t);
           } else if (k < jobs_t + jobs_r) {
             kind = kJobPairR;
-            first = (k - jobs_t) * kChunkR;
-            last = min(first + kChunkR, n_r);
+            first = (k - jobs_t) * q.cr;
+            last = min(first + q.cr, n_r);
           } else if (k < jobs_t + jobs_r + jobs_s) {
             kind = kJobPairS;
-            first = (k - jobs_t - jobs_r) * kChunkH;
-            last = min(first + kChunkH, n_s);
+            first = (k - jobs_t - jobs_r) * q.ch;
+            last = min(first + q.ch, n_s);
           } else {
             kind = kJobPairQ;
-            first = (k - jobs_t - jobs_r - jobs_s) * kChunkH;
-            last = min(first + kChunkH, n_q);
+            first = (k - jobs_t - jobs_r - jobs_s) * q.ch;
+            last = min(first + q.ch, n_q);
           }
           q.job[q_base + k] = make_uint4(kind, uint32_t(smp), first, last);
         }
@@ -1029,6 +1032,11 @@ int launch_sampled(const hm_graph* H, int k, const uint32_t* const idx[5], const
   a.q.tail = H->sample_hist + 257;
   a.q.head = H->sample_hist + 258;
   a.q.tcls = nullptr;
+  const uint32_t scale = sample_chunk_scale();
+  a.q.ct = std::max<uint32_t>(1, kChunkT / scale);
+  a.q.cr = std::max<uint32_t>(1, kChunkR / scale);
+  a.q.cx = std::max<uint32_t>(1, kChunkX / scale);
+  a.q.ch = std::max<uint32_t>(1, kChunkH / scale);
   struct Release {
     void* p[2] = {nullptr, nullptr};
     ~Release() {
@@ -1037,7 +1045,7 @@ int launch_sampled(const hm_graph* H, int k, const uint32_t* const idx[5], const
     }
   } rel;
   if (k == 4 && !bits) {
-    a.q.cap = 32ull * (a.d.S[2] + a.d.S[3]) + 65536;
+    a.q.cap = 32ull * scale * (a.d.S[2] + a.d.S[3]) + 65536;
     HM_TRY(dalloc(&rel.p[0], a.q.cap * sizeof(uint4)));
     HM_TRY(dalloc(&rel.p[1], (3 * a.d.S[2] + 1) * sizeof(uint32_t)));
     a.q.job = static_cast<uint4*>(rel.p[0]);

@@ -64,12 +64,21 @@ def test_mlp_gradient_matches_oracle(hm, n):
     assert close.mean() > 0.995
 
 
-def test_contributions_match_oracle(hm):
+@pytest.mark.parametrize("path", ["bits", "hash", "queued"])
+def test_contributions_match_oracle(hm, path):
+    """Per-hyperedge contributions (one sample row each); without bit rows, and
+    with every long walk through the work queue."""
     h = W.random_small(6000, 30, 180, {2: 0.5, 3: 0.3, 4: 0.2})
     nh = core.normalise(h)
     t = table(4)
-    with hm.hm_graph_create(h.members, h.offsets, h.n_nodes) as g:
-        y = hm.hm_contrib(g, 4).cpu().numpy()
+    hm.hm_set_option(hm.HM_OPT_BITSET_MAX_NODES, 8192 if path == "bits" else 0)
+    hm.hm_set_option(hm.HM_OPT_SAMPLE_CHUNK_SCALE, 1024 if path == "queued" else 1)
+    try:
+        with hm.hm_graph_create(h.members, h.offsets, h.n_nodes) as g:
+            y = hm.hm_contrib(g, 4).cpu().numpy()
+    finally:
+        hm.hm_set_option(hm.HM_OPT_BITSET_MAX_NODES, 8192)
+        hm.hm_set_option(hm.HM_OPT_SAMPLE_CHUNK_SCALE, 1)
     want = []
     for j in (2, 3, 4):
         for i in range(nh.count(j)):

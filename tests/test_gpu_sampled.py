@@ -172,3 +172,59 @@ def test_unbiased_over_32_seeds(hm):
     mre = stats.mean_relative_error(runs, exact)
     print(f"mean relative error over 32 seeds at 10%: {mre:.4f}")
     assert mre < 0.05
+
+
+@pytest.fixture
+def queued(hm):
+    """No bit rows and the smallest work chunks: the long walks of every sample
+    go through the work queue and its drain launch."""
+    hm.hm_set_option(hm.HM_OPT_SAMPLE_CHUNK_SCALE, 1024)
+    try:
+        yield
+    finally:
+        hm.hm_set_option(hm.HM_OPT_SAMPLE_CHUNK_SCALE, 1)
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_work_queue_matches_oracle(hm, queued, seed):
+    mixes = [{2: 0.6, 3: 0.3, 4: 0.1}, {2: 0.3, 3: 0.4, 4: 0.3}]
+    h = W.random_small(4500 + seed, 20 + (seed * 13) % 40, 120 + (seed * 71) % 300, mixes[seed % 2])
+    nh = core.normalise(h)
+    with _graph(hm, h, False) as g:
+        for fraction in (0.3, 1.0):
+            est, raw = hm.count_sampled(g, 4, fraction, seed * 3 + 2, 0)
+            want_raw, want_est, _, _ = _oracle_sampled(nh, 4, fraction, seed * 3 + 2)
+            assert np.array_equal(raw.cpu().numpy(), want_raw), fraction
+            assert np.array_equal(est.cpu().numpy(), want_est), fraction
+
+
+def test_work_queue_heavy_tailed(hm, queued):
+    h = W.scaled_communication(0.004, 0)
+    nh = core.normalise(h)
+    want_raw, want_est, _, _ = _oracle_sampled(nh, 4, 0.2, 31)
+    with _graph(hm, h, False) as g:
+        est, raw = hm.count_sampled(g, 4, 0.2, 31, 0)
+        # twice in a row: the queue counters are left clear
+        est2, raw2 = hm.count_sampled(g, 4, 0.2, 31, 0)
+    assert np.array_equal(raw.cpu().numpy(), want_raw)
+    assert np.array_equal(raw2.cpu().numpy(), want_raw)
+    assert np.array_equal(est2.cpu().numpy(), want_est)
+
+
+def test_work_queue_census(hm, queued):
+    h = W.scaled_communication(0.004, 0)
+    exact = _golden("communication_scaled_0.004", 4)
+    with _graph(hm, h, False) as g:
+        st = g.stats()
+        samples = {j: np.arange(st[f"n{j}"]) for j in range(2, 5)}
+        est, raw = hm.count_sampled_indices(g, 4, samples)
+        countmax = np.array([hm.hm_class_info(4, c)[2] for c in range(len(exact))])
+    assert np.array_equal(raw.cpu().numpy(), exact * countmax)
+    assert np.array_equal(est.cpu().numpy(), exact.astype(np.float32))
+
+
+def test_chunk_scale_option_bounds(hm):
+    for bad in (0, 1025):
+        with pytest.raises(hm.HMError):
+            hm.hm_set_option(hm.HM_OPT_SAMPLE_CHUNK_SCALE, bad)
+    hm.hm_set_option(hm.HM_OPT_SAMPLE_CHUNK_SCALE, 1)
