@@ -11,7 +11,7 @@
 #include <algorithm>
 #include <vector>
 
-#include "hm_internal.h"
+#include "hm_device.h"
 
 namespace hm {
 namespace {
@@ -28,8 +28,6 @@ struct DevFlags {
   uint32_t err_edge;
   unsigned long long singletons;
   unsigned long long duplicates;
-  uint32_t max_deg2;
-  uint32_t max_deg3;
 };
 
 constexpr int kRegSort = 16;
@@ -131,99 +129,285 @@ __global__ void k_dedup_insert(const uint32_t* __restrict__ sm, const uint64_t* 
   }
 }
 
-// Flags of first occurrences, per size class, and the member counts of the
-// unique hyperedges (for the member offsets of the unique list).
-__global__ void k_first_flags(const uint32_t* __restrict__ sm, const uint64_t* __restrict__ off,
-                              const uint32_t* __restrict__ size, const unsigned long long* __restrict__ hash,
-                              uint64_t n_edges, const uint32_t* __restrict__ slots, unsigned long long mask,
-                              uint32_t* f_all, uint32_t* f2, uint32_t* f3, uint32_t* f4,
-                              unsigned long long* msize, DevFlags* flags) {
+// Ingest works in tiles of 256 input hyperedges: k_first_tiles marks first
+// occurrences and counts, per tile, the unique hyperedges (all, of size 2, 3,
+// 4) and their members; k_tile_scan turns the tile counts into tile offsets;
+// k_gather_tiles recomputes each hyperedge's position inside its tile and
+// writes it out.
+constexpr uint32_t kTile = 256;
+constexpr int kTileN = 5;   // unique, unique of size 2, 3, 4, members of the unique
+
+__device__ inline bool first_occurrence(const uint32_t* sm, const uint64_t* off, const uint32_t* size,
+                                        const unsigned long long* hash, uint64_t i, const uint32_t* slots,
+                                        unsigned long long mask) {
+  unsigned long long pos = hash[i] & mask;
+  while (true) {
+    const uint32_t cur = slots[pos];
+    if (cur == kEmpty32) return false;   // cannot happen: i was inserted
+    if (same_tuple(sm, off, size, hash, cur, i)) return cur == uint32_t(i);
+    pos = (pos + 1) & mask;
+  }
+}
+
+// Per-thread contribution of hyperedge i to the five tile counters.
+__device__ inline void tile_terms(uint32_t first, uint32_t s, uint32_t t[kTileN]) {
+  t[0] = first;
+  t[1] = first && s == 2;
+  t[2] = first && s == 3;
+  t[3] = first && s == 4;
+  t[4] = first ? s : 0;
+}
+
+__global__ void __launch_bounds__(kTile) k_first_tiles(const uint32_t* __restrict__ sm,
+                                                        const uint64_t* __restrict__ off,
+                                                        const uint32_t* __restrict__ size,
+                                                        const unsigned long long* __restrict__ hash, uint64_t n_edges,
+                                                        const uint32_t* __restrict__ slots, unsigned long long mask,
+                                                        uint8_t* __restrict__ first_out,
+                                                        unsigned long long* __restrict__ tile_cnt, DevFlags* flags) {
+  __shared__ unsigned long long part[kTileN][kTile / kWave];
+  const uint64_t i = uint64_t(blockIdx.x) * kTile + threadIdx.x;
+  uint32_t first = 0, s = 0;
   unsigned long long singles = 0, dups = 0;
-  for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n_edges;
-       i += uint64_t(gridDim.x) * blockDim.x) {
-    const uint32_t s = size[i];
-    bool first = false;
+  if (i < n_edges) {
+    s = size[i];
     if (s >= 2) {
-      unsigned long long pos = hash[i] & mask;
-      while (true) {
-        uint32_t cur = slots[pos];
-        if (cur == kEmpty32) break;  // cannot happen: i was inserted
-        if (same_tuple(sm, off, size, hash, cur, i)) {
-          first = (cur == uint32_t(i));
-          break;
-        }
-        pos = (pos + 1) & mask;
-      }
-      if (!first) ++dups;
+      first = first_occurrence(sm, off, size, hash, i, slots, mask);
+      dups = !first;
     } else if (s == 1) {
-      ++singles;
+      singles = 1;
     }
-    f_all[i] = first;
-    f2[i] = first && s == 2;
-    f3[i] = first && s == 3;
-    f4[i] = first && s == 4;
-    msize[i] = first ? s : 0;
+    first_out[i] = uint8_t(first);
   }
-  if (singles) atomicAdd(&flags->singletons, singles);
-  if (dups) atomicAdd(&flags->duplicates, dups);
+  uint32_t t[kTileN];
+  tile_terms(first, s, t);
+  const int wv = threadIdx.x / kWave;
+  for (int k = 0; k < kTileN; ++k) {
+    const unsigned long long w = wave_sum((unsigned long long)t[k]);
+    if ((threadIdx.x & (kWave - 1)) == 0) part[k][wv] = w;
+  }
+  singles = wave_sum(singles);
+  dups = wave_sum(dups);
+  if ((threadIdx.x & (kWave - 1)) == 0) {
+    if (singles) atomicAdd(&flags->singletons, singles);
+    if (dups) atomicAdd(&flags->duplicates, dups);
+  }
+  __syncthreads();
+  if (threadIdx.x < kTileN) {
+    unsigned long long sum = 0;
+    for (int q = 0; q < int(kTile / kWave); ++q) sum += part[threadIdx.x][q];
+    tile_cnt[uint64_t(blockIdx.x) * kTileN + threadIdx.x] = sum;
+  }
 }
 
-__global__ void k_gather(const uint32_t* __restrict__ sm, const uint64_t* __restrict__ off,
-                         const uint32_t* __restrict__ size, uint64_t n_edges, const uint32_t* __restrict__ f_all,
-                         const uint32_t* __restrict__ p_all, const uint32_t* __restrict__ p2,
-                         const uint32_t* __restrict__ p3, const uint32_t* __restrict__ p4,
-                         const unsigned long long* __restrict__ moff, uint32_t* e2, uint32_t* e3, uint32_t* e4,
-                         uint32_t* all_members, unsigned long long* all_off) {
-  for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n_edges;
+// Exclusive scan of the tile counters in place (one workgroup of 1024), and
+// the five totals.
+__global__ void __launch_bounds__(1024) k_tile_scan(unsigned long long* __restrict__ tile_cnt, uint64_t n_tiles,
+                                                    unsigned long long* __restrict__ totals) {
+  __shared__ unsigned long long wsum[1024 / kWave];
+  __shared__ unsigned long long carry;
+  const uint32_t lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+  for (int k = 0; k < kTileN; ++k) {
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (uint64_t c0 = 0; c0 < n_tiles; c0 += 1024) {
+      const uint64_t t = c0 + threadIdx.x;
+      const unsigned long long x = t < n_tiles ? tile_cnt[t * kTileN + k] : 0;
+      // inclusive wave scan
+      unsigned long long y = x;
+      for (int d = 1; d < kWave; d <<= 1) {
+        const uint32_t lo = __shfl_up(uint32_t(y), d, kWave), hi = __shfl_up(uint32_t(y >> 32), d, kWave);
+        if (int(lane) >= d) y += (unsigned long long)hi << 32 | lo;
+      }
+      if (lane == kWave - 1) wsum[wv] = y;
+      __syncthreads();
+      unsigned long long before = carry;
+      for (uint32_t q = 0; q < wv; ++q) before += wsum[q];
+      if (t < n_tiles) tile_cnt[t * kTileN + k] = before + y - x;
+      __syncthreads();
+      if (threadIdx.x == 1023) carry = before + y;
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) totals[k] = carry;
+    __syncthreads();
+  }
+}
+
+// Write the unique hyperedges out, in first-occurrence order, with everything
+// that only needs them once: the strata e2/e3/e4, the list of all unique
+// hyperedges with its member offsets, the hash-set entries, the adjacency bit
+// rows (when kept) and the node degrees of the pairwise graph and of the
+// incidence lists.
+struct GatherOut {
+  uint32_t *e2, *e3, *e4, *all_members;
+  unsigned long long* all_off;
+  Set64 hs2;
+  Set128 hs3, hs4;
+  uint32_t* bits;
+  uint32_t W;
+  uint32_t *deg2, *deg3, *deg4;
+  unsigned long long n_unique, n_members;
+};
+
+__global__ void __launch_bounds__(kTile) k_gather_tiles(const uint32_t* __restrict__ sm,
+                                                         const uint64_t* __restrict__ off,
+                                                         const uint32_t* __restrict__ size, uint64_t n_edges,
+                                                         const uint8_t* __restrict__ first_in,
+                                                         const unsigned long long* __restrict__ tile_off,
+                                                         GatherOut g) {
+  __shared__ uint32_t part[kTileN][kTile / kWave];
+  const uint64_t i = uint64_t(blockIdx.x) * kTile + threadIdx.x;
+  uint32_t first = 0, s = 0;
+  if (i < n_edges) {
+    first = first_in[i];
+    s = size[i];
+  }
+  uint32_t t[kTileN];
+  tile_terms(first, s, t);
+  uint32_t pre[kTileN];
+  const int wv = threadIdx.x / kWave;
+  for (int k = 0; k < kTileN; ++k) {
+    uint32_t tot;
+    pre[k] = wave_exclusive_scan(t[k], &tot);
+    if ((threadIdx.x & (kWave - 1)) == 0) part[k][wv] = tot;
+  }
+  __syncthreads();
+  if (!first) return;
+  unsigned long long pos[kTileN];
+  for (int k = 0; k < kTileN; ++k) {
+    unsigned long long p = tile_off[uint64_t(blockIdx.x) * kTileN + k] + pre[k];
+    for (int q = 0; q < wv; ++q) p += part[k][q];
+    pos[k] = p;
+  }
+  const uint32_t* m = sm + off[i];
+  for (uint32_t j = 0; j < s; ++j) g.all_members[pos[4] + j] = m[j];
+  g.all_off[pos[0]] = pos[4];
+  if (pos[0] + 1 == g.n_unique) g.all_off[g.n_unique] = g.n_members;
+  if (s == 2) {
+    const uint32_t a = m[0], b = m[1];
+    g.e2[2 * pos[1]] = a;
+    g.e2[2 * pos[1] + 1] = b;
+    const unsigned long long key = key2(a, b);
+    unsigned long long h = mix64(key) & g.hs2.mask;
+    while (atomicCAS(g.hs2.slot + h, kEmpty64, key) != kEmpty64) h = (h + 1) & g.hs2.mask;
+    if (g.bits) {
+      atomicOr(&g.bits[uint64_t(a) * g.W + (b >> 5)], 1u << (b & 31));
+      atomicOr(&g.bits[uint64_t(b) * g.W + (a >> 5)], 1u << (a & 31));
+    }
+    atomicAdd(&g.deg2[a], 1u);
+    atomicAdd(&g.deg2[b], 1u);
+  } else if (s == 3 || s == 4) {
+    uint32_t* e = s == 3 ? g.e3 + 3 * pos[2] : g.e4 + 4 * pos[3];
+    for (uint32_t j = 0; j < s; ++j) e[j] = m[j];
+    const Key128 key = s == 3 ? key3(m[0], m[1], m[2]) : key4(m[0], m[1], m[2], m[3]);
+    const Set128& set = s == 3 ? g.hs3 : g.hs4;
+    unsigned long long h = hash128(key) & set.mask;
+    while (atomicCAS(set.slot + 2 * h, kEmpty64, key.hi) != kEmpty64) h = (h + 1) & set.mask;
+    set.slot[2 * h + 1] = key.lo;
+    uint32_t* deg = s == 3 ? g.deg3 : g.deg4;
+    for (uint32_t j = 0; j < s; ++j) atomicAdd(&deg[m[j]], 1u);
+  }
+}
+
+// Up to eight fills in one launch.
+struct FillRegions {
+  void* ptr[8];
+  unsigned long long count[8];
+  unsigned long long value[8];
+  uint32_t wide[8];   // 1: 64-bit elements, 0: 32-bit
+  uint32_t n;
+};
+
+__global__ void k_multi_fill(FillRegions r) {
+  const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
+  for (uint32_t k = 0; k < r.n; ++k) {
+    for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < r.count[k]; i += stride) {
+      if (r.wide[k]) static_cast<unsigned long long*>(r.ptr[k])[i] = r.value[k];
+      else static_cast<uint32_t*>(r.ptr[k])[i] = uint32_t(r.value[k]);
+    }
+  }
+}
+
+// Exclusive scans of the three degree arrays into row offsets (n + 1
+// entries each) and, for the incidence lists, fill cursors.  One workgroup
+// of 1024 per array.
+__global__ void __launch_bounds__(1024) k_scan_degrees(const uint32_t* __restrict__ d0, uint32_t* __restrict__ o0,
+                                                       const uint32_t* __restrict__ d1, uint32_t* __restrict__ o1,
+                                                       uint32_t* __restrict__ c1, const uint32_t* __restrict__ d2,
+                                                       uint32_t* __restrict__ o2, uint32_t* __restrict__ c2, uint32_t n) {
+  __shared__ uint32_t wsum[1024 / kWave];
+  __shared__ uint32_t carry;
+  const uint32_t* d = blockIdx.x == 0 ? d0 : blockIdx.x == 1 ? d1 : d2;
+  uint32_t* o = blockIdx.x == 0 ? o0 : blockIdx.x == 1 ? o1 : o2;
+  uint32_t* c = blockIdx.x == 0 ? nullptr : blockIdx.x == 1 ? c1 : c2;
+  const uint32_t lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+  if (threadIdx.x == 0) carry = 0;
+  __syncthreads();
+  for (uint32_t c0 = 0; c0 < n; c0 += 1024) {
+    const uint32_t t = c0 + threadIdx.x;
+    const uint32_t x = t < n ? d[t] : 0;
+    uint32_t tot;
+    const uint32_t ex = wave_exclusive_scan(x, &tot);
+    if (lane == 0) wsum[wv] = tot;
+    __syncthreads();
+    uint32_t before = carry;
+    for (uint32_t q = 0; q < wv; ++q) before += wsum[q];
+    if (t < n) {
+      o[t] = before + ex;
+      if (c) c[t] = before + ex;
+    }
+    __syncthreads();
+    if (threadIdx.x == 1023) carry = before + ex + x;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) o[n] = carry;
+}
+
+// Sorted pairwise rows read off the adjacency bit rows: one wavefront per
+// node, 64 words at a time, set bits written in ascending order.
+__global__ void k_rows_from_bits(const uint32_t* __restrict__ bits, uint32_t n, uint32_t W,
+                                 const uint32_t* __restrict__ row_off, uint32_t* __restrict__ adj) {
+  const uint32_t lane = threadIdx.x & (kWave - 1);
+  const uint64_t wave = (uint64_t(blockIdx.x) * blockDim.x + threadIdx.x) / kWave;
+  const uint64_t n_waves = uint64_t(gridDim.x) * blockDim.x / kWave;
+  for (uint64_t x = wave; x < n; x += n_waves) {
+    uint32_t base = row_off[x];
+    const uint32_t* row = bits + x * W;
+    for (uint32_t w0 = 0; w0 < W; w0 += kWave) {
+      uint32_t word = w0 + lane < W ? row[w0 + lane] : 0u;
+      uint32_t tot;
+      uint32_t p = base + wave_exclusive_scan(__popc(word), &tot);
+      while (word) {
+        adj[p++] = ((w0 + lane) << 5) | uint32_t(__ffs(word) - 1);
+        word &= word - 1;
+      }
+      base += tot;
+    }
+  }
+}
+
+// Incidence lists of the 3- and 4-node hyperedges (positions in any order).
+__global__ void k_inc_fill(const uint32_t* __restrict__ e3, uint64_t n3, uint32_t* cur3, uint32_t* idx3,
+                           const uint32_t* __restrict__ e4, uint64_t n4, uint32_t* cur4, uint32_t* idx4) {
+  for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n3 + n4;
        i += uint64_t(gridDim.x) * blockDim.x) {
-    if (!f_all[i]) continue;
-    const uint32_t s = size[i];
-    const uint32_t* m = sm + off[i];
-    if (s == 2) {
-      e2[2ull * p2[i]] = m[0];
-      e2[2ull * p2[i] + 1] = m[1];
-    } else if (s == 3) {
-      for (int j = 0; j < 3; ++j) e3[3ull * p3[i] + j] = m[j];
-    } else if (s == 4) {
-      for (int j = 0; j < 4; ++j) e4[4ull * p4[i] + j] = m[j];
+    if (i < n3) {
+      for (int j = 0; j < 3; ++j) idx3[atomicAdd(&cur3[e3[3 * i + j]], 1u)] = uint32_t(i);
+    } else {
+      const uint64_t q = i - n3;
+      for (int j = 0; j < 4; ++j) idx4[atomicAdd(&cur4[e4[4 * q + j]], 1u)] = uint32_t(q);
     }
-    const unsigned long long mo = moff[i];
-    for (uint32_t j = 0; j < s; ++j) all_members[mo + j] = m[j];
-    all_off[p_all[i]] = mo;
-  }
-}
-
-__global__ void k_set64_insert(const uint32_t* __restrict__ e2, uint64_t n, Set64 set) {
-  for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += uint64_t(gridDim.x) * blockDim.x) {
-    const unsigned long long key = key2(e2[2 * i], e2[2 * i + 1]);
-    unsigned long long pos = mix64(key) & set.mask;
-    while (atomicCAS(set.slot + pos, kEmpty64, key) != kEmpty64) pos = (pos + 1) & set.mask;
-  }
-}
-
-// Keys are unique, so a slot is claimed by its high word alone; the low word
-// is written by the claimant.  No kernel reads the set while it is built.
-template <int J>
-__global__ void k_set128_insert(const uint32_t* __restrict__ e, uint64_t n, Set128 set) {
-  for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += uint64_t(gridDim.x) * blockDim.x) {
-    const uint32_t* t = e + J * i;
-    const Key128 key = (J == 3) ? key3(t[0], t[1], t[2]) : key4(t[0], t[1], t[2], t[3]);
-    unsigned long long pos = hash128(key) & set.mask;
-    while (atomicCAS(set.slot + 2 * pos, kEmpty64, key.hi) != kEmpty64) pos = (pos + 1) & set.mask;
-    set.slot[2 * pos + 1] = key.lo;
   }
 }
 
 __global__ void k_pair_keys(const uint32_t* __restrict__ e2, uint64_t n, int bits_per_node,
-                            unsigned long long* keys, uint32_t* vals, uint32_t* deg) {
+                            unsigned long long* keys, uint32_t* vals) {
   for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += uint64_t(gridDim.x) * blockDim.x) {
     const uint32_t a = e2[2 * i], b = e2[2 * i + 1];
     keys[2 * i] = ((unsigned long long)a << bits_per_node) | b;
     keys[2 * i + 1] = ((unsigned long long)b << bits_per_node) | a;
     vals[2 * i] = uint32_t(i);
     vals[2 * i + 1] = uint32_t(i);
-    atomicAdd(&deg[a], 1u);
-    atomicAdd(&deg[b], 1u);
   }
 }
 
@@ -231,34 +415,6 @@ __global__ void k_pair_adj(const unsigned long long* __restrict__ keys, uint64_t
                            uint32_t* adj) {
   for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += uint64_t(gridDim.x) * blockDim.x)
     adj[i] = uint32_t(keys[i] & low_mask);
-}
-
-__global__ void k_max(const uint32_t* __restrict__ v, uint64_t n, uint32_t* out) {
-  uint32_t m = 0;
-  for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += uint64_t(gridDim.x) * blockDim.x)
-    m = max(m, v[i]);
-  for (int d = kWave / 2; d > 0; d >>= 1) m = max(m, uint32_t(__shfl_xor(int(m), d, kWave)));
-  if ((threadIdx.x & (kWave - 1)) == 0) atomicMax(out, m);
-}
-
-template <int J>
-__global__ void k_incidence_count(const uint32_t* __restrict__ e, uint64_t n, uint32_t* deg) {
-  for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += uint64_t(gridDim.x) * blockDim.x)
-    for (int j = 0; j < J; ++j) atomicAdd(&deg[e[J * i + j]], 1u);
-}
-
-template <int J>
-__global__ void k_incidence_fill(const uint32_t* __restrict__ e, uint64_t n, uint32_t* cursor, uint32_t* idx) {
-  for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += uint64_t(gridDim.x) * blockDim.x)
-    for (int j = 0; j < J; ++j) idx[atomicAdd(&cursor[e[J * i + j]], 1u)] = uint32_t(i);
-}
-
-__global__ void k_bits(const uint32_t* __restrict__ e2, uint64_t n, uint32_t words, uint32_t* bits) {
-  for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += uint64_t(gridDim.x) * blockDim.x) {
-    const uint32_t a = e2[2 * i], b = e2[2 * i + 1];
-    atomicOr(&bits[uint64_t(a) * words + (b >> 5)], 1u << (b & 31));
-    atomicOr(&bits[uint64_t(b) * words + (a >> 5)], 1u << (a & 31));
-  }
 }
 
 unsigned grid_for(uint64_t n, unsigned block = 256) {
@@ -298,39 +454,6 @@ int node_bits(uint32_t n_nodes) {
   return b;
 }
 
-int build_csr_from_incidence(hm_graph* H, const uint32_t* e, uint64_t n, int J, uint32_t** off_out,
-                             uint32_t** idx_out, uint32_t* max_deg, hipStream_t st) {
-  Temps tmp;
-  uint32_t *deg = nullptr, *cursor = nullptr, *dmax = nullptr;
-  HM_TRY(tmp.get(&deg, H->n_nodes));
-  HM_TRY(tmp.get(&dmax, 1));
-  HM_TRY(owned(off_out, uint64_t(H->n_nodes) + 1));
-  HM_TRY(owned(idx_out, uint64_t(J) * n));
-  HM_TRY(fill_u32(deg, 0, H->n_nodes, st));
-  HM_TRY(fill_u32(dmax, 0, 1, st));
-  if (n) {
-    if (J == 3)
-      k_incidence_count<3><<<grid_for(n), 256, 0, st>>>(e, n, deg);
-    else
-      k_incidence_count<4><<<grid_for(n), 256, 0, st>>>(e, n, deg);
-    HM_HIP(hipGetLastError());
-  }
-  HM_TRY(scan_exclusive_u32(deg, *off_out, H->n_nodes, *off_out + H->n_nodes, st));
-  k_max<<<grid_for(H->n_nodes), 256, 0, st>>>(deg, H->n_nodes, dmax);
-  HM_HIP(hipGetLastError());
-  HM_TRY(tmp.get(&cursor, H->n_nodes));
-  HM_HIP(hipMemcpyAsync(cursor, *off_out, sizeof(uint32_t) * H->n_nodes, hipMemcpyDeviceToDevice, st));
-  if (n) {
-    if (J == 3)
-      k_incidence_fill<3><<<grid_for(n), 256, 0, st>>>(e, n, cursor, *idx_out);
-    else
-      k_incidence_fill<4><<<grid_for(n), 256, 0, st>>>(e, n, cursor, *idx_out);
-    HM_HIP(hipGetLastError());
-  }
-  HM_HIP(hipMemcpyAsync(max_deg, dmax, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
-  return HM_OK;
-}
-
 int build(hm_graph* H, const uint32_t* members_in, const uint64_t* offsets_in, uint64_t n_edges, int mem_kind,
           hipStream_t st) {
   Temps tmp;
@@ -366,20 +489,36 @@ int build(hm_graph* H, const uint32_t* members_in, const uint64_t* offsets_in, u
     return HM_EUNSUPPORTED;
   }
   const uint64_t E = n_edges;
+  const uint64_t n_tiles = (E + kTile - 1) / kTile;
   DevFlags* flags = nullptr;
-  uint32_t *sm = nullptr, *size = nullptr;
-  unsigned long long* hash = nullptr;
+  uint32_t *sm = nullptr, *size = nullptr, *slots = nullptr;
+  unsigned long long *hash = nullptr, *tile_cnt = nullptr, *totals = nullptr;
+  uint8_t* first = nullptr;
+  const unsigned long long cap = pow2_capacity(E);
   HM_TRY(tmp.get(&flags, 1));
   HM_TRY(tmp.get(&sm, nnz));
   HM_TRY(tmp.get(&size, E));
   HM_TRY(tmp.get(&hash, E));
-  DevFlags init{0, 0xFFFFFFFFu, 0, 0, 0, 0};
+  HM_TRY(tmp.get(&slots, cap));
+  HM_TRY(tmp.get(&first, E));
+  HM_TRY(tmp.get(&tile_cnt, n_tiles * kTileN));
+  HM_TRY(tmp.get(&totals, kTileN));
+  DevFlags init{0, 0xFFFFFFFFu, 0, 0};
   HM_HIP(hipMemcpyAsync(flags, &init, sizeof(init), hipMemcpyHostToDevice, st));
+  HM_TRY(fill_u32(slots, kEmpty32, cap, st));
+  HM_TRY(fill_u64(totals, 0, kTileN, st));
   if (E) {
+    // validate and sort; collapse repeated hyperedges onto first occurrences
     k_prepare<<<grid_for(E), 256, 0, st>>>(members, offsets, E, nnz, H->n_nodes, sm, size, hash, flags);
+    k_dedup_insert<<<grid_for(E), 256, 0, st>>>(sm, offsets, size, hash, E, slots, cap - 1);
+    k_first_tiles<<<unsigned(n_tiles), kTile, 0, st>>>(sm, offsets, size, hash, E, slots, cap - 1, first, tile_cnt,
+                                                       flags);
+    k_tile_scan<<<1, 1024, 0, st>>>(tile_cnt, n_tiles, totals);
     HM_HIP(hipGetLastError());
   }
+  unsigned long long tot[kTileN] = {0, 0, 0, 0, 0};
   DevFlags got;
+  HM_HIP(hipMemcpyAsync(tot, totals, sizeof(tot), hipMemcpyDeviceToHost, st));
   HM_HIP(hipMemcpyAsync(&got, flags, sizeof(got), hipMemcpyDeviceToHost, st));
   HM_HIP(hipStreamSynchronize(st));
   if (got.err) {
@@ -390,69 +529,23 @@ int build(hm_graph* H, const uint32_t* members_in, const uint64_t* offsets_in, u
     set_error("invalid hypergraph: %s (first offending hyperedge index %u)", what, got.err_edge);
     return HM_EINVAL;
   }
-
-  // collapse repeated hyperedges onto first occurrences
-  const unsigned long long cap = pow2_capacity(E);
-  uint32_t* slots = nullptr;
-  HM_TRY(tmp.get(&slots, cap));
-  HM_TRY(fill_u32(slots, kEmpty32, cap, st));
-  uint32_t *f_all, *f2, *f3, *f4, *p_all, *p2, *p3, *p4, *tot;
-  unsigned long long *msize, *moff;
-  HM_TRY(tmp.get(&f_all, E));
-  HM_TRY(tmp.get(&f2, E));
-  HM_TRY(tmp.get(&f3, E));
-  HM_TRY(tmp.get(&f4, E));
-  HM_TRY(tmp.get(&p_all, E));
-  HM_TRY(tmp.get(&p2, E));
-  HM_TRY(tmp.get(&p3, E));
-  HM_TRY(tmp.get(&p4, E));
-  HM_TRY(tmp.get(&tot, 4));
-  HM_TRY(tmp.get(&msize, E + 1));
-  HM_TRY(tmp.get(&moff, E + 1));
-  HM_TRY(fill_u32(tot, 0, 4, st));
-  if (E) {
-    k_dedup_insert<<<grid_for(E), 256, 0, st>>>(sm, offsets, size, hash, E, slots, cap - 1);
-    HM_HIP(hipGetLastError());
-    k_first_flags<<<grid_for(E), 256, 0, st>>>(sm, offsets, size, hash, E, slots, cap - 1, f_all, f2, f3, f4,
-                                               msize, flags);
-    HM_HIP(hipGetLastError());
-    HM_TRY(scan_exclusive_u32(f_all, p_all, E, tot + 0, st));
-    HM_TRY(scan_exclusive_u32(f2, p2, E, tot + 1, st));
-    HM_TRY(scan_exclusive_u32(f3, p3, E, tot + 2, st));
-    HM_TRY(scan_exclusive_u32(f4, p4, E, tot + 3, st));
-    HM_TRY(fill_u64(msize + E, 0, 1, st));
-    HM_TRY(scan_exclusive_u64(msize, moff, E + 1, st));
-  }
-  uint32_t totals[4] = {0, 0, 0, 0};
-  unsigned long long n_members = 0;
-  HM_HIP(hipMemcpyAsync(totals, tot, sizeof(totals), hipMemcpyDeviceToHost, st));
-  if (E) HM_HIP(hipMemcpyAsync(&n_members, moff + E, sizeof(n_members), hipMemcpyDeviceToHost, st));
-  HM_HIP(hipMemcpyAsync(&got, flags, sizeof(got), hipMemcpyDeviceToHost, st));
-  HM_HIP(hipStreamSynchronize(st));
-  H->n_unique = totals[0];
-  H->n_by_size[2] = totals[1];
-  H->n_by_size[3] = totals[2];
-  H->n_by_size[4] = totals[3];
-  H->n_by_size[5] = totals[0] - totals[1] - totals[2] - totals[3];
+  H->n_unique = tot[0];
+  H->n_by_size[2] = tot[1];
+  H->n_by_size[3] = tot[2];
+  H->n_by_size[4] = tot[3];
+  H->n_by_size[5] = tot[0] - tot[1] - tot[2] - tot[3];
   H->n_singletons = got.singletons;
   H->n_duplicates = got.duplicates;
-  H->n_unique_members = n_members;
+  H->n_unique_members = tot[4];
   const uint64_t n2 = H->n_by_size[2], n3 = H->n_by_size[3], n4 = H->n_by_size[4];
+  const uint64_t N = H->n_nodes;
 
+  // everything the unique hyperedges are written into
   HM_TRY(owned(&H->e2, 2 * n2));
   HM_TRY(owned(&H->e3, 3 * n3));
   HM_TRY(owned(&H->e4, 4 * n4));
-  HM_TRY(owned(&H->all_members, n_members));
+  HM_TRY(owned(&H->all_members, H->n_unique_members));
   HM_TRY(owned(&H->all_off, H->n_unique + 1));
-  if (E) {
-    k_gather<<<grid_for(E), 256, 0, st>>>(sm, offsets, size, E, f_all, p_all, p2, p3, p4, moff, H->e2, H->e3, H->e4,
-                                          H->all_members, H->all_off);
-    HM_HIP(hipGetLastError());
-  }
-  HM_HIP(hipMemcpyAsync(H->all_off + H->n_unique, &n_members, sizeof(n_members), hipMemcpyHostToDevice, st));
-  HM_HIP(hipStreamSynchronize(st));
-
-  // hash sets of hyperedges of size 2, 3, 4
   const unsigned long long c2 = pow2_capacity(n2), c3 = pow2_capacity(n3), c4 = pow2_capacity(n4);
   HM_TRY(owned(&H->hs2.slot, c2));
   HM_TRY(owned(&H->hs3.slot, 2 * c3));
@@ -460,61 +553,106 @@ int build(hm_graph* H, const uint32_t* members_in, const uint64_t* offsets_in, u
   H->hs2.mask = c2 - 1;
   H->hs3.mask = c3 - 1;
   H->hs4.mask = c4 - 1;
-  HM_TRY(fill_u64(H->hs2.slot, kEmpty64, c2, st));
-  HM_TRY(fill_u64(H->hs3.slot, kEmpty64, 2 * c3, st));
-  HM_TRY(fill_u64(H->hs4.slot, kEmpty64, 2 * c4, st));
-  if (n2) k_set64_insert<<<grid_for(n2), 256, 0, st>>>(H->e2, n2, H->hs2);
-  if (n3) k_set128_insert<3><<<grid_for(n3), 256, 0, st>>>(H->e3, n3, H->hs3);
-  if (n4) k_set128_insert<4><<<grid_for(n4), 256, 0, st>>>(H->e4, n4, H->hs4);
+  const bool keep_bits = H->n_nodes <= bitset_max_nodes();
+  if (keep_bits) {
+    H->words = (H->n_nodes + 31) / 32;
+    HM_TRY(owned(&H->bits, N * H->words));
+  }
+  uint32_t *deg2 = nullptr, *deg3 = nullptr, *deg4 = nullptr, *cur3 = nullptr, *cur4 = nullptr;
+  HM_TRY(tmp.get(&deg2, N));
+  HM_TRY(tmp.get(&deg3, N));
+  HM_TRY(tmp.get(&deg4, N));
+  HM_TRY(tmp.get(&cur3, N));
+  HM_TRY(tmp.get(&cur4, N));
+  HM_TRY(owned(&H->g2_off, N + 1));
+  HM_TRY(owned(&H->g2_adj, 2 * n2));
+  HM_TRY(owned(&H->i3_off, N + 1));
+  HM_TRY(owned(&H->i3_idx, 3 * n3));
+  HM_TRY(owned(&H->i4_off, N + 1));
+  HM_TRY(owned(&H->i4_idx, 4 * n4));
+  HM_TRY(owned(&H->hist, 4 * 256));
+  HM_TRY(owned(&H->sample_hist, 256 + 8));
+  {
+    FillRegions r{};
+    auto add = [&r](void* p, unsigned long long n, unsigned long long v, uint32_t wide) {
+      r.ptr[r.n] = p;
+      r.count[r.n] = n;
+      r.value[r.n] = v;
+      r.wide[r.n] = wide;
+      ++r.n;
+    };
+    add(H->hs2.slot, c2, kEmpty64, 1);
+    add(H->hs3.slot, 2 * c3, kEmpty64, 1);
+    add(H->hs4.slot, 2 * c4, kEmpty64, 1);
+    add(H->sample_hist, 256 + 8, 0, 1);
+    add(deg2, N, 0, 0);
+    add(deg3, N, 0, 0);
+    add(deg4, N, 0, 0);
+    if (keep_bits) add(H->bits, N * H->words, 0, 0);
+    unsigned long long most = 0;
+    for (uint32_t k = 0; k < r.n; ++k) most = std::max(most, r.count[k]);
+    k_multi_fill<<<grid_for(most), 256, 0, st>>>(r);
+  }
+  if (E) {
+    GatherOut g;
+    g.e2 = H->e2;
+    g.e3 = H->e3;
+    g.e4 = H->e4;
+    g.all_members = H->all_members;
+    g.all_off = H->all_off;
+    g.hs2 = H->hs2;
+    g.hs3 = H->hs3;
+    g.hs4 = H->hs4;
+    g.bits = H->bits;
+    g.W = H->words;
+    g.deg2 = deg2;
+    g.deg3 = deg3;
+    g.deg4 = deg4;
+    g.n_unique = H->n_unique;
+    g.n_members = H->n_unique_members;
+    k_gather_tiles<<<unsigned(n_tiles), kTile, 0, st>>>(sm, offsets, size, E, first, tile_cnt, g);
+  }
+  if (H->n_unique == 0) HM_TRY(fill_u64(H->all_off, 0, 1, st));
   HM_HIP(hipGetLastError());
 
-  // pairwise graph: ascending CSR rows from a radix sort of directed pairs
-  {
-    const int B = node_bits(H->n_nodes);
-    const uint64_t m = 2 * n2;
-    unsigned long long *keys, *keys_tmp;
-    uint32_t *vals, *vals_tmp, *deg, *dmax;
-    HM_TRY(tmp.get(&keys, m));
-    HM_TRY(tmp.get(&keys_tmp, m));
-    HM_TRY(owned(&H->g2_eid, m));
-    vals = H->g2_eid;
-    HM_TRY(tmp.get(&vals_tmp, m));
-    HM_TRY(tmp.get(&deg, H->n_nodes));
-    HM_TRY(tmp.get(&dmax, 1));
-    HM_TRY(fill_u32(deg, 0, H->n_nodes, st));
-    HM_TRY(fill_u32(dmax, 0, 1, st));
-    HM_TRY(owned(&H->g2_off, uint64_t(H->n_nodes) + 1));
-    HM_TRY(owned(&H->g2_adj, m));
-    if (n2) {
-      k_pair_keys<<<grid_for(n2), 256, 0, st>>>(H->e2, n2, B, keys, vals, deg);
+  // row offsets: pairwise rows, incidence lists of 3- and 4-node hyperedges
+  if (N <= 64 * 1024) {
+    k_scan_degrees<<<3, 1024, 0, st>>>(deg2, H->g2_off, deg3, H->i3_off, cur3, deg4, H->i4_off, cur4, uint32_t(N));
+    HM_HIP(hipGetLastError());
+  } else {
+    HM_TRY(scan_exclusive_u32(deg2, H->g2_off, N, H->g2_off + N, st));
+    HM_TRY(scan_exclusive_u32(deg3, H->i3_off, N, H->i3_off + N, st));
+    HM_TRY(scan_exclusive_u32(deg4, H->i4_off, N, H->i4_off + N, st));
+    HM_TRY(copy_u32(H->i3_off, cur3, N, st));
+    HM_TRY(copy_u32(H->i4_off, cur4, N, st));
+  }
+  if (n3 + n4) {
+    k_inc_fill<<<grid_for(n3 + n4), 256, 0, st>>>(H->e3, n3, cur3, H->i3_idx, H->e4, n4, cur4, H->i4_idx);
+    HM_HIP(hipGetLastError());
+  }
+  if (n2) {
+    if (keep_bits) {
+      // ascending rows straight from the bit rows
+      k_rows_from_bits<<<grid_for(N * kWave), 256, 0, st>>>(H->bits, uint32_t(N), H->words, H->g2_off, H->g2_adj);
       HM_HIP(hipGetLastError());
-      HM_TRY(radix_sort_pairs(keys, vals, keys_tmp, vals_tmp, m, 2 * B, st));
+    } else {
+      // ascending rows from a radix sort of directed pairs, with the position
+      // in e2 of each entry's pair
+      const int B = node_bits(H->n_nodes);
+      const uint64_t m = 2 * n2;
+      unsigned long long *keys, *keys_tmp;
+      uint32_t* vals_tmp;
+      HM_TRY(tmp.get(&keys, m));
+      HM_TRY(tmp.get(&keys_tmp, m));
+      HM_TRY(tmp.get(&vals_tmp, m));
+      HM_TRY(owned(&H->g2_eid, m));
+      k_pair_keys<<<grid_for(n2), 256, 0, st>>>(H->e2, n2, B, keys, H->g2_eid);
+      HM_HIP(hipGetLastError());
+      HM_TRY(radix_sort_pairs(keys, H->g2_eid, keys_tmp, vals_tmp, m, 2 * B, st));
       k_pair_adj<<<grid_for(m), 256, 0, st>>>(keys, m, (1ull << B) - 1, H->g2_adj);
       HM_HIP(hipGetLastError());
     }
-    HM_TRY(scan_exclusive_u32(deg, H->g2_off, H->n_nodes, H->g2_off + H->n_nodes, st));
-    k_max<<<grid_for(H->n_nodes), 256, 0, st>>>(deg, H->n_nodes, dmax);
-    HM_HIP(hipGetLastError());
-    HM_HIP(hipMemcpyAsync(&H->max_deg2, dmax, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
-    HM_HIP(hipStreamSynchronize(st));
   }
-  HM_TRY(build_csr_from_incidence(H, H->e3, n3, 3, &H->i3_off, &H->i3_idx, &H->max_deg3, st));
-  uint32_t max_deg4 = 0;
-  HM_TRY(build_csr_from_incidence(H, H->e4, n4, 4, &H->i4_off, &H->i4_idx, &max_deg4, st));
-
-  if (H->n_nodes <= bitset_max_nodes()) {
-    H->words = (H->n_nodes + 31) / 32;
-    const uint64_t nw = uint64_t(H->n_nodes) * H->words;
-    HM_TRY(owned(&H->bits, nw));
-    HM_TRY(fill_u32(H->bits, 0, nw, st));
-    if (n2) {
-      k_bits<<<grid_for(n2), 256, 0, st>>>(H->e2, n2, H->words, H->bits);
-      HM_HIP(hipGetLastError());
-    }
-  }
-  HM_TRY(owned(&H->hist, 4 * 256));
-  HM_TRY(owned(&H->sample_hist, 256 + 8));
-  HM_TRY(fill_u64(H->sample_hist, 0, 256 + 8, st));
   HM_HIP(hipStreamSynchronize(st));
   return HM_OK;
 }

@@ -218,11 +218,9 @@ struct hm_graph {
   uint32_t* g2_off = nullptr;   // n_nodes + 1
   uint32_t* g2_adj = nullptr;   // 2 * n2
   uint32_t* g2_eid = nullptr;   // 2 * n2: position in e2 of the pair of each adjacency entry
-  uint32_t max_deg2 = 0;
   // node -> incident 3-node hyperedges (indices into e3)
   uint32_t* i3_off = nullptr;
   uint32_t* i3_idx = nullptr;
-  uint32_t max_deg3 = 0;
   // node -> incident 4-node hyperedges (indices into e4)
   uint32_t* i4_off = nullptr;
   uint32_t* i4_idx = nullptr;

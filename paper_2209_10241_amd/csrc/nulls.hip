@@ -981,8 +981,9 @@ int enqueue_count(const hm_graph* H, NullPlan& P, const Chunks& ch, hipStream_t 
   return HM_OK;
 }
 
+// The seed-dependent part of a call (the real counts in P.real do not depend
+// on it and are counted once, before capture).
 int enqueue_all(const hm_graph* H, NullPlan& P, hipStream_t st) {
-  HM_TRY(count_exact_impl(H, P.k, P.real, st));
   HM_TRY(enqueue_stubs(H, P, 0, st));
   HM_TRY(enqueue_ingest(H, P, st));
   HM_TRY(enqueue_count(H, P, P.chunks, st));
@@ -1109,7 +1110,9 @@ int count_nulls_impl(hm_graph* H, int k, uint32_t R, uint64_t seed, int64_t* rea
   if (!P) {
     HM_TRY(make_plan(H, k, R, &P));
     H->null_plan = P;
-    // first run outside a graph: ingest the copies once and tune the tile sizes
+    // first run outside a graph: the real counts, then ingest the copies once
+    // and tune the tile sizes
+    HM_TRY(count_exact_impl(H, k, P->real, st));
     unsigned long long s0 = seed;
     HM_HIP(hipMemcpyAsync(P->seed, &s0, sizeof(s0), hipMemcpyHostToDevice, st));
     HM_TRY(enqueue_stubs(H, *P, 0, st));
