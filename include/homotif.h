@@ -91,7 +91,12 @@ int hm_pattern_class(int k, uint32_t pattern, int* cls);
  * adjacency used by the enumeration.
  *   members  n_members = offsets[n_edges] node ids; offsets n_edges+1 values
  *   mem_kind HM_MEM_HOST or HM_MEM_DEVICE: where members and offsets live
- *   stream   hipStream_t for the build (the call synchronises it before return)
+ *   stream   hipStream_t for the build.  The call returns once the input has
+ *            been validated and the sizes are known (hm_graph_stats is then
+ *            exact); the rest of the build stays enqueued on the stream, so
+ *            later calls on the same stream see the finished graph, and work
+ *            on another stream must first wait for this one.  The caller's
+ *            members/offsets buffers may be reused as soon as it returns.
  *   out      receives the handle
  * Errors: HM_EINVAL for an empty hyperedge, a node id >= n_nodes, a node
  * repeated inside a hyperedge, non-monotone offsets or n_nodes = 0. */

@@ -169,18 +169,27 @@ int device_luts(int device, const uint8_t** lut4, const uint8_t** lut3) {
 
 // Device memory cache: blocks are rounded up to a power of two and, when
 // released, kept on a free list of their (device, size class) for the next
-// allocation of that class instead of being returned to the runtime.  Every
-// release happens after the work that used the block has been ordered
-// before any later user (the library synchronises its stream before
-// releasing temporaries), so a cached block is never handed out while in use.
+// allocation of that class instead of being returned to the runtime.  A
+// block released with dfree is assumed idle (its users were synchronised);
+// one released with dfree_on stays pending until an event recorded on the
+// given stream after its last use has completed, so it is never handed out
+// while work enqueued before the release may still touch it.
 namespace {
 struct BlockInfo {
   int device;
   size_t bytes;
 };
+struct Pending {
+  void* p;
+  BlockInfo info;
+  hipEvent_t ev;
+};
 std::mutex g_pool_mu;
 std::map<std::pair<int, size_t>, std::vector<void*>> g_free;
 std::unordered_map<void*, BlockInfo> g_live;
+std::vector<Pending> g_pending;
+std::map<int, std::vector<hipEvent_t>> g_events;   // idle events per device
+std::unordered_map<hipEvent_t, size_t> g_event_users;   // pending blocks per event
 size_t g_cached_bytes = 0;
 constexpr size_t kMaxCachedBytes = size_t(8) << 30;
 
@@ -188,6 +197,35 @@ size_t size_class(size_t bytes) {
   size_t c = 256;
   while (c < bytes) c <<= 1;
   return c;
+}
+
+// caller holds g_pool_mu
+void cache_block(void* p, const BlockInfo& info) {
+  if (g_cached_bytes + info.bytes > kMaxCachedBytes) {
+    (void)hipFree(p);
+    return;
+  }
+  g_free[{info.device, info.bytes}].push_back(p);
+  g_cached_bytes += info.bytes;
+}
+
+// caller holds g_pool_mu: pending blocks whose event has completed become free
+void reap_pending() {
+  for (size_t i = 0; i < g_pending.size();) {
+    Pending& q = g_pending[i];
+    if (hipEventQuery(q.ev) == hipSuccess) {
+      cache_block(q.p, q.info);
+      if (--g_event_users[q.ev] == 0) {
+        g_event_users.erase(q.ev);
+        g_events[q.info.device].push_back(q.ev);
+      }
+      q = g_pending.back();
+      g_pending.pop_back();
+    } else {
+      ++i;
+    }
+  }
+  (void)hipGetLastError();
 }
 }  // namespace
 
@@ -201,6 +239,7 @@ int dalloc(void** p, size_t bytes) {
   const size_t cls = size_class(bytes ? bytes : 1);
   {
     std::lock_guard<std::mutex> lock(g_pool_mu);
+    if (!g_pending.empty()) reap_pending();
     auto it = g_free.find({dev, cls});
     if (it != g_free.end() && !it->second.empty()) {
       *p = it->second.back();
@@ -229,13 +268,44 @@ void dfree(void* p) {
   if (it == g_live.end()) return;
   const BlockInfo info = it->second;
   g_live.erase(it);
-  if (g_cached_bytes + info.bytes > kMaxCachedBytes) {
-    (void)hipFree(p);
+  cache_block(p, info);
+}
+
+void dfree_on(void* const* ps, size_t n, hipStream_t st) {
+  std::lock_guard<std::mutex> lock(g_pool_mu);
+  std::vector<std::pair<void*, BlockInfo>> blocks;
+  for (size_t i = 0; i < n; ++i) {
+    if (!ps[i]) continue;
+    auto it = g_live.find(ps[i]);
+    if (it == g_live.end()) continue;
+    blocks.emplace_back(ps[i], it->second);
+    g_live.erase(it);
+  }
+  if (blocks.empty()) return;
+  // one event for the batch, shared by its blocks
+  const int dev = blocks.front().second.device;
+  hipEvent_t ev = nullptr;
+  auto& pool = g_events[dev];
+  if (!pool.empty()) {
+    ev = pool.back();
+    pool.pop_back();
+  } else if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+    (void)hipGetLastError();
+    ev = nullptr;
+  }
+  if (!ev || hipEventRecord(ev, st) != hipSuccess) {
+    // no event: wait for the stream instead
+    (void)hipGetLastError();
+    (void)hipStreamSynchronize(st);
+    if (ev) pool.push_back(ev);
+    for (auto& b : blocks) cache_block(b.first, b.second);
     return;
   }
-  g_free[{info.device, info.bytes}].push_back(p);
-  g_cached_bytes += info.bytes;
+  g_event_users[ev] += blocks.size();
+  for (auto& b : blocks) g_pending.push_back(Pending{b.first, b.second, ev});
 }
+
+void dfree_on(void* p, hipStream_t st) { dfree_on(&p, 1, st); }
 
 }  // namespace hm
 

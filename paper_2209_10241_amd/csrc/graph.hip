@@ -424,12 +424,13 @@ unsigned grid_for(uint64_t n, unsigned block = 256) {
   return unsigned(g);
 }
 
-// RAII holder for temporary device buffers of the build
+// RAII holder for temporary device buffers of the build, released after the
+// work enqueued on the build's stream
 struct Temps {
+  hipStream_t st;
   std::vector<void*> ptrs;
-  ~Temps() {
-    for (void* p : ptrs) dfree(p);
-  }
+  explicit Temps(hipStream_t s) : st(s) {}
+  ~Temps() { dfree_on(ptrs.data(), ptrs.size(), st); }
   template <typename T>
   int get(T** p, uint64_t count) {
     void* q = nullptr;
@@ -456,7 +457,7 @@ int node_bits(uint32_t n_nodes) {
 
 int build(hm_graph* H, const uint32_t* members_in, const uint64_t* offsets_in, uint64_t n_edges, int mem_kind,
           hipStream_t st) {
-  Temps tmp;
+  Temps tmp(st);
   uint64_t nnz = 0;
   const uint32_t* members = members_in;
   const uint64_t* offsets = offsets_in;
@@ -490,23 +491,43 @@ int build(hm_graph* H, const uint32_t* members_in, const uint64_t* offsets_in, u
   }
   const uint64_t E = n_edges;
   const uint64_t n_tiles = (E + kTile - 1) / kTile;
-  DevFlags* flags = nullptr;
+  // validation flags and the five totals share one block, read back at once
+  struct Report {
+    DevFlags flags;
+    unsigned long long totals[kTileN];
+  };
+  static_assert(sizeof(Report) % 8 == 0, "report is cleared as 64-bit words");
+  Report* report = nullptr;
   uint32_t *sm = nullptr, *size = nullptr, *slots = nullptr;
-  unsigned long long *hash = nullptr, *tile_cnt = nullptr, *totals = nullptr;
+  unsigned long long *hash = nullptr, *tile_cnt = nullptr;
   uint8_t* first = nullptr;
   const unsigned long long cap = pow2_capacity(E);
-  HM_TRY(tmp.get(&flags, 1));
+  HM_TRY(tmp.get(&report, 1));
   HM_TRY(tmp.get(&sm, nnz));
   HM_TRY(tmp.get(&size, E));
   HM_TRY(tmp.get(&hash, E));
   HM_TRY(tmp.get(&slots, cap));
   HM_TRY(tmp.get(&first, E));
   HM_TRY(tmp.get(&tile_cnt, n_tiles * kTileN));
-  HM_TRY(tmp.get(&totals, kTileN));
-  DevFlags init{0, 0xFFFFFFFFu, 0, 0};
-  HM_HIP(hipMemcpyAsync(flags, &init, sizeof(init), hipMemcpyHostToDevice, st));
-  HM_TRY(fill_u32(slots, kEmpty32, cap, st));
-  HM_TRY(fill_u64(totals, 0, kTileN, st));
+  DevFlags* flags = &report->flags;
+  unsigned long long* totals = report->totals;
+  {
+    FillRegions r{};
+    r.ptr[0] = report;
+    r.count[0] = sizeof(Report) / 8;
+    r.value[0] = 0;
+    r.wide[0] = 1;
+    r.ptr[1] = &report->flags.err_edge;   // no offending hyperedge yet
+    r.count[1] = 1;
+    r.value[1] = 0xFFFFFFFFu;
+    r.wide[1] = 0;
+    r.ptr[2] = slots;
+    r.count[2] = cap;
+    r.value[2] = kEmpty32;
+    r.wide[2] = 0;
+    r.n = 3;
+    k_multi_fill<<<grid_for(cap), 256, 0, st>>>(r);
+  }
   if (E) {
     // validate and sort; collapse repeated hyperedges onto first occurrences
     k_prepare<<<grid_for(E), 256, 0, st>>>(members, offsets, E, nnz, H->n_nodes, sm, size, hash, flags);
@@ -516,11 +537,11 @@ int build(hm_graph* H, const uint32_t* members_in, const uint64_t* offsets_in, u
     k_tile_scan<<<1, 1024, 0, st>>>(tile_cnt, n_tiles, totals);
     HM_HIP(hipGetLastError());
   }
-  unsigned long long tot[kTileN] = {0, 0, 0, 0, 0};
-  DevFlags got;
-  HM_HIP(hipMemcpyAsync(tot, totals, sizeof(tot), hipMemcpyDeviceToHost, st));
-  HM_HIP(hipMemcpyAsync(&got, flags, sizeof(got), hipMemcpyDeviceToHost, st));
+  Report rep;
+  HM_HIP(hipMemcpyAsync(&rep, report, sizeof(rep), hipMemcpyDeviceToHost, st));
   HM_HIP(hipStreamSynchronize(st));
+  const DevFlags& got = rep.flags;
+  const unsigned long long* tot = rep.totals;
   if (got.err) {
     const char* what = (got.err & kErrOffsets) ? "offsets decrease or exceed offsets[n_edges]"
                        : (got.err & kErrEmpty) ? "an empty hyperedge"
@@ -653,7 +674,8 @@ int build(hm_graph* H, const uint32_t* members_in, const uint64_t* offsets_in, u
       HM_HIP(hipGetLastError());
     }
   }
-  HM_HIP(hipStreamSynchronize(st));
+  // no wait: later calls on the stream are ordered after the build, and the
+  // temporaries return to the cache only once it has run
   return HM_OK;
 }
 
@@ -774,6 +796,7 @@ int hm_graph_export(const hm_graph* H, int j, uint32_t* out) {
   }
   const uint32_t* src = j == 2 ? H->e2 : j == 3 ? H->e3 : H->e4;
   const uint64_t n = H->n_by_size[j] * uint64_t(j);
+  HM_HIP(hipDeviceSynchronize());   // the build may still be running on its stream
   if (n) HM_HIP(hipMemcpy(out, src, n * sizeof(uint32_t), hipMemcpyDeviceToHost));
   return HM_OK;
 }

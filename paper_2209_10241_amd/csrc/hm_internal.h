@@ -176,7 +176,12 @@ class ProfileScope {
 
 // ----------------------------------------------------------------- device allocations
 int dalloc(void** p, size_t bytes);
+// release a block whose users are synchronised
 void dfree(void* p);
+// release blocks that work already enqueued on st may still use (one event
+// recorded on st for the batch)
+void dfree_on(void* p, hipStream_t st);
+void dfree_on(void* const* ps, size_t n, hipStream_t st);
 
 // Order-k counts of the pairs-only shapes and of case (b) without bit rows
 // into H->hist (case (a) is counted by the caller).
