@@ -106,19 +106,20 @@ __device__ void b4_edge_hash(uint32_t a, uint32_t b, uint32_t c, const uint32_t*
   }
 }
 
-// Bit-row version.  The wavefront builds, in LDS, bit sets of the nodes v for
-// which {a,b,v}, {a,c,v}, {b,c,v} are 3-node hyperedges (from the incident
-// 3-node hyperedges of a and b) and for which e u {v} is a 4-node hyperedge
-// (from the incident 4-node hyperedges of a).  The candidates are the union of
-// these with the pairwise neighbours of a, b and c, compacted with popcount
-// prefix sums; fill-in of e u {v} is then a set of bit tests.
+// Bit-row version, counting instead of listing.  The wavefront builds, in
+// LDS, bit sets of the nodes v with {a,b,v}, {a,c,v} or {b,c,v} a 3-node
+// hyperedge (T_ab, T_ac, T_bc, from the incident 3-node hyperedges of a and b)
+// and with e u {v} a 4-node hyperedge (Q, from those of a).  Any other v
+// leaves e the only hyperedge of size >= 3 in e u {v}, so those v are counted
+// per pairwise combination (av, bv, cv) with popcounts over the rows of a, b,
+// c; the nodes of the T sets outside Q are classified one by one.
 template <bool OWN>
-__device__ void b4_edge_bits(uint32_t a, uint32_t b, uint32_t c, const uint32_t* __restrict__ e3,
-                             const uint32_t* __restrict__ e4, const uint32_t* __restrict__ i3_off,
-                             const uint32_t* __restrict__ i3_idx, const uint32_t* __restrict__ i4_off,
-                             const uint32_t* __restrict__ i4_idx, const uint32_t* __restrict__ bits, uint32_t W,
-                             B4Scratch& sc, const uint8_t* lut, unsigned long long* h_main,
-                             unsigned long long* h_sub) {
+__device__ void b4_edge_bits_count(uint32_t a, uint32_t b, uint32_t c, const uint32_t* __restrict__ e3,
+                                   const uint32_t* __restrict__ e4, const uint32_t* __restrict__ i3_off,
+                                   const uint32_t* __restrict__ i3_idx, const uint32_t* __restrict__ i4_off,
+                                   const uint32_t* __restrict__ i4_idx, const uint32_t* __restrict__ bits,
+                                   uint32_t W, B4Scratch& sc, const uint8_t* lut, unsigned long long* h_main,
+                                   unsigned long long* h_sub) {
   const int lane = threadIdx.x & (kWave - 1);
   uint32_t* Tab = sc.sets[0];
   uint32_t* Tac = sc.sets[1];
@@ -148,29 +149,66 @@ __device__ void b4_edge_bits(uint32_t a, uint32_t b, uint32_t c, const uint32_t*
   const uint32_t p4 = i4_off[a], l4 = i4_off[a + 1] - p4;
   for (uint32_t t = lane; t < l4; t += kWave) {
     const uint32_t f = i4_idx[p4 + t];
-    const uint32_t m[4] = {e4[4ull * f], e4[4ull * f + 1], e4[4ull * f + 2], e4[4ull * f + 3]};
-    int hits = 0;
-    uint32_t v = 0;
-    for (int j = 0; j < 4; ++j) {
-      if (m[j] == a || m[j] == b || m[j] == c) ++hits; else v = m[j];
-    }
-    if (hits == 3) atomicOr(&Q[v >> 5], 1u << (v & 31));
+    const uint32_t m0 = e4[4ull * f], m1 = e4[4ull * f + 1], m2 = e4[4ull * f + 2], m3 = e4[4ull * f + 3];
+    const bool i0 = m0 == a || m0 == b || m0 == c, i1 = m1 == a || m1 == b || m1 == c;
+    const bool i2 = m2 == a || m2 == b || m2 == c, i3 = m3 == a || m3 == b || m3 == c;
+    if (int(i0) + int(i1) + int(i2) + int(i3) != 3) continue;
+    const uint32_t v = !i0 ? m0 : (!i1 ? m1 : (!i2 ? m2 : m3));
+    atomicOr(&Q[v >> 5], 1u << (v & 31));
   }
   wave_sync();
   const uint32_t pab = (Ra[b >> 5] >> (b & 31)) & 1u, pac = (Ra[c >> 5] >> (c & 31)) & 1u,
                  pbc = (Rb[c >> 5] >> (c & 31)) & 1u;
   const uint32_t base_p = pab | (pac << 1) | (pbc << 2) | (1u << 3);
+  // the ordinary fourth nodes, per combination
+  uint32_t n1 = 0, n2 = 0, n3 = 0, n4 = 0, n5 = 0, n6 = 0, n7 = 0;
+  for (uint32_t w = lane; w < W; w += kWave) {
+    const uint32_t ra = Ra[w], rb = Rb[w], rc = Rc[w];
+    uint32_t excl = Tab[w] | Tac[w] | Tbc[w] | Q[w];
+    if ((a >> 5) == w) excl |= 1u << (a & 31);
+    if ((b >> 5) == w) excl |= 1u << (b & 31);
+    if ((c >> 5) == w) excl |= 1u << (c & 31);
+    const uint32_t m = (ra | rb | rc) & ~excl;
+    n1 += __popc(m & ra & ~rb & ~rc);
+    n2 += __popc(m & ~ra & rb & ~rc);
+    n3 += __popc(m & ra & rb & ~rc);
+    n4 += __popc(m & ~ra & ~rb & rc);
+    n5 += __popc(m & ra & ~rb & rc);
+    n6 += __popc(m & ~ra & rb & rc);
+    n7 += __popc(m & ra & rb & rc);
+  }
+  uint32_t n[8];
+  n[1] = n1; n[2] = n2; n[3] = n3; n[4] = n4; n[5] = n5; n[6] = n6; n[7] = n7;
+#pragma unroll
+  for (int k = 1; k < 8; ++k) {
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) n[k] += __shfl_xor(n[k], o, kWave);
+  }
+  if (lane == 0) {
+#pragma unroll
+    for (uint32_t cmb = 1; cmb < 8; ++cmb) {
+      if (!n[cmb]) continue;
+      const uint32_t pt = base_p | ((cmb & 1u) << 4) | (((cmb >> 1) & 1u) << 5) | ((cmb >> 2) << 7);
+      atomicAdd(&h_main[lut[pt]], (unsigned long long)n[cmb]);
+      if (h_sub) {
+        const uint8_t g = lut[pt & kPairBits4];
+        if (g != 0xFF) atomicAdd(&h_sub[g], (unsigned long long)n[cmb]);
+      }
+    }
+  }
+  // the fourth nodes on another 3-node hyperedge (not on a 4-node one), one by one
   for (uint32_t w0 = 0; w0 < W; w0 += kChunkWords) {
     const uint32_t w = w0 + lane;
     uint32_t cw = 0;
     if (w < W) {
-      cw = Ra[w] | Rb[w] | Rc[w] | Tab[w] | Tac[w] | Tbc[w];
+      cw = (Tab[w] | Tac[w] | Tbc[w]) & ~Q[w];
       if ((a >> 5) == w) cw &= ~(1u << (a & 31));
       if ((b >> 5) == w) cw &= ~(1u << (b & 31));
       if ((c >> 5) == w) cw &= ~(1u << (c & 31));
     }
     uint32_t total;
     uint32_t pos = wave_exclusive_scan(__popc(cw), &total);
+    if (total == 0) continue;   // wave-uniform
     while (cw) {
       const uint32_t bit = __ffs(cw) - 1;
       cw &= cw - 1;
@@ -180,7 +218,6 @@ __device__ void b4_edge_bits(uint32_t a, uint32_t b, uint32_t c, const uint32_t*
     for (uint32_t t = lane; t < total; t += kWave) {
       const uint32_t v = list[t];
       const uint32_t vw = v >> 5, vb = v & 31;
-      if ((Q[vw] >> vb) & 1u) continue;                    // a 4-node hyperedge
       const uint32_t tab = (Tab[vw] >> vb) & 1u, tac = (Tac[vw] >> vb) & 1u, tbc = (Tbc[vw] >> vb) & 1u;
       if (OWN && ((tab && v < c) || (tac && v < b) || (tbc && v < a))) continue;   // an earlier 3-node hyperedge
       const uint32_t qa = (Ra[vw] >> vb) & 1u, qb = (Rb[vw] >> vb) & 1u, qc = (Rc[vw] >> vb) & 1u;

@@ -91,8 +91,8 @@ __device__ inline void b4_item(const View& v, uint64_t i, B4Scratch* sc, const u
                                unsigned long long* h_sub) {
   const uint32_t a = v.e3[3 * i], b = v.e3[3 * i + 1], c = v.e3[3 * i + 2];
   if (v.bits)
-    b4_edge_bits<true>(a, b, c, v.e3, v.e4, v.i3_off, v.i3_idx, v.i4_off, v.i4_idx, v.bits, v.W, *sc, lut, h_main,
-                       h_sub);
+    b4_edge_bits_count<true>(a, b, c, v.e3, v.e4, v.i3_off, v.i3_idx, v.i4_off, v.i4_idx, v.bits, v.W, *sc, lut,
+                             h_main, h_sub);
   else
     b4_edge_hash<true>(a, b, c, v.e3, v.g2_off, v.g2_adj, v.i3_off, v.i3_idx, v.hs2, v.hs3, v.hs4, lut, h_main, h_sub);
 }
