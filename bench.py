@@ -54,7 +54,7 @@ def _unit_counts(e2: np.ndarray, e3: np.ndarray, n_nodes: int, words: int) -> di
         t = e3.astype(np.int64)
         cand = int(deg2[t[:, 0]].sum() + deg2[t[:, 1]].sum() + deg2[t[:, 2]].sum()
                    + deg3[t[:, 0]].sum() + deg3[t[:, 1]].sum())
-    return {"c4_word_tasks": int(ys) * words, "b4_candidates": cand}
+    return {"c4_word_tasks": int(ys) * words, "b4_word_tasks": int(len(e3)) * words, "b4_candidates": cand}
 
 
 def exact_source_digest() -> str:
@@ -277,18 +277,16 @@ def main() -> int:
     traffic = measured_traffic()
     dom = max(kernels, key=lambda k: kernels[k]["avg_ms"])
     avg_s = kernels[dom]["avg_ms"] / 1e3
-    if dom == "k_case_c4_bits":
-        # per (pair, y, word) task: 7 popcounts and about 17 further logic/add
-        # integer operations on three adjacency words held in cache
-        ops = units["c4_word_tasks"] * 24
+    if dom == "k_exact4_bits":
+        # the fused counting launch; its work is integer logic on adjacency words
+        # held in cache: per (pair, y, word) task of case (c) 7 popcounts and
+        # about 17 further logic/add operations, per (3-node hyperedge, word) of
+        # case (b) 7 popcounts and about 21 further operations
+        ops = units["c4_word_tasks"] * 24 + units["b4_word_tasks"] * 28
         roof = {"bound": "alu", "achieved": ops / avg_s / 1e12, "peak": ALU_PEAK_TOPS, "unit": "Tops/s",
-                "frac": ops / avg_s / 1e12 / ALU_PEAK_TOPS, "traffic": traffic.get("k_case_c4_bits")}
+                "frac": ops / avg_s / 1e12 / ALU_PEAK_TOPS, "traffic": traffic.get(dom)}
     else:
-        # per generator instance: a 4-byte adjacency entry, 3 pair keys (8 B) and
-        # 3 triple + 1 quadruple keys (16 B) of fill-in
-        byts = units["b4_candidates"] * 92
-        roof = {"bound": "hbm", "achieved": byts / avg_s / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": byts / avg_s / 1e9 / HBM_PEAK_GBS, "traffic": traffic.get("k_case_b4")}
+        raise RuntimeError(f"unexpected dominant kernel {dom}")
     roof["kernel"] = dom
 
     large = None if (args.no_large or args.exact_only) else large_workloads(hm, W, torch)

@@ -9,6 +9,10 @@
 // Fig. 3b) and one read of the pattern->class table (Section 4.3 Fig. 3a)
 // held in LDS; per-class counters live in LDS and are flushed to device
 // memory with one atomic per class per workgroup.
+#include <algorithm>
+#include <map>
+#include <mutex>
+#include <tuple>
 #include <vector>
 
 #include "hm_items.h"
@@ -34,46 +38,6 @@ __global__ void __launch_bounds__(kThreads) k_case_a4(View v, uint64_t n4, const
   flush(h_sub, hist + kSub, 256);
 }
 
-// (b) at order 4: one wavefront per 3-node hyperedge.
-__global__ void __launch_bounds__(kThreads) k_case_b4(View v, uint64_t n3, const uint8_t* __restrict__ lut_g,
-                                                      unsigned long long* __restrict__ hist) {
-  __shared__ uint8_t lut[2048];
-  __shared__ unsigned long long h_main[256], h_sub[256];
-  __shared__ B4Scratch scratch[kWavesPerBlock];
-  load_lut(lut, lut_g, 2048);
-  h_main[threadIdx.x] = 0;
-  h_sub[threadIdx.x] = 0;
-  __syncthreads();
-  const int wv = threadIdx.x / kWave;
-  const uint64_t wave = uint64_t(blockIdx.x) * kWavesPerBlock + wv;
-  const uint64_t n_waves = uint64_t(gridDim.x) * kWavesPerBlock;
-  for (uint64_t i = wave; i < n3; i += n_waves) b4_item(v, i, &scratch[wv], lut, h_main, h_sub);
-  __syncthreads();
-  flush(h_main, hist + kMain, 256);
-  flush(h_sub, hist + kSub, 256);
-}
-
-// (c) at order 4: one wavefront per pair {r < x} of G2.
-__global__ void __launch_bounds__(kThreads) k_case_c4_bits(View v, uint64_t n2, const uint8_t* __restrict__ lut_g,
-                                                           unsigned long long* __restrict__ hist) {
-  __shared__ uint8_t lut[2048];
-  __shared__ unsigned long long h_g2[256];
-  __shared__ uint32_t ylist[kWavesPerBlock][kWave];
-  load_lut(lut, lut_g, 2048);
-  h_g2[threadIdx.x] = 0;
-  __syncthreads();
-  const int wv = threadIdx.x / kWave;
-  const uint64_t wave = uint64_t(blockIdx.x) * kWavesPerBlock + wv;
-  const uint64_t n_waves = uint64_t(gridDim.x) * kWavesPerBlock;
-  const C4Lanes L = c4_lanes(v.W);
-  C4Acc acc;
-  c4_zero(acc);
-  for (uint64_t i = wave; i < n2; i += n_waves) c4_bits_item(v, v.e2[2 * i], v.e2[2 * i + 1], L, ylist[wv], acc);
-  c4_flush(acc, lut, h_g2);
-  __syncthreads();
-  flush(h_g2, hist + kG2, 256);
-}
-
 // (a) at order 3: one thread per 3-node hyperedge.
 __global__ void __launch_bounds__(kThreads) k_case_a3(View v, uint64_t n3, const uint8_t* __restrict__ lut_g,
                                                       unsigned long long* __restrict__ hist) {
@@ -90,37 +54,112 @@ __global__ void __launch_bounds__(kThreads) k_case_a3(View v, uint64_t n3, const
   flush(h_sub, hist + kSub, 256);
 }
 
-// (c) at order 3 with bit rows: one thread per (pair, word).
-__global__ void __launch_bounds__(kThreads) k_case_c3_bits(View v, uint64_t n2, const uint8_t* __restrict__ lut_g,
-                                                           unsigned long long* __restrict__ hist) {
-  __shared__ uint8_t lut[16];
-  __shared__ unsigned long long h_g2[256];
-  load_lut(lut, lut_g, 16);
-  h_g2[threadIdx.x] = 0;
-  __syncthreads();
-  C3Acc acc{0, 0, 0};
-  const uint64_t tasks = n2 * v.W;
-  for (uint64_t t = uint64_t(blockIdx.x) * kThreads + threadIdx.x; t < tasks; t += uint64_t(gridDim.x) * kThreads) {
-    const uint64_t i = t / v.W;
-    c3_bits_word(v, v.e2[2 * i], v.e2[2 * i + 1], uint32_t(t % v.W), acc);
-  }
-  c3_flush(acc, lut, h_g2);
-  __syncthreads();
-  flush(h_g2, hist + kG2, 256);
-}
-
 // counts[c] = main[c] + (c pairs-only ? g2[c] - sub[c] : 0), as int64
 struct ClassMask {
   unsigned long long w[4];
 };
 
-__global__ void k_combine(const unsigned long long* __restrict__ hist, int n_classes, ClassMask pairs_only,
+// (one workgroup of 256 threads; leaves hist zero)
+__global__ void k_combine(unsigned long long* __restrict__ hist, int n_classes, ClassMask pairs_only,
                           int64_t* __restrict__ counts) {
   const int c = threadIdx.x;
-  if (c >= n_classes) return;
-  unsigned long long v = hist[kMain + c];
-  if ((pairs_only.w[c >> 6] >> (c & 63)) & 1ull) v += hist[kG2 + c] - hist[kSub + c];
-  counts[c] = int64_t(v);
+  const unsigned long long m = hist[kMain + c], s = hist[kSub + c], g = hist[kG2 + c];
+  if (c < n_classes) {
+    unsigned long long v = m;
+    if ((pairs_only.w[c >> 6] >> (c & 63)) & 1ull) v += g - s;
+    counts[c] = int64_t(v);
+  }
+  hist[kMain + c] = 0;
+  hist[kSub + c] = 0;
+  hist[kG2 + c] = 0;
+}
+
+// All generators of one order in a single launch (bit rows), sized to the
+// workgroups resident at once.  The work of the three cases is laid out as
+// one list that every wavefront (order 4) or thread (order 3) strides over,
+// so each takes a like share of every case and no case waits for another.
+// The counters go to the main, sub and G2 regions of hist; k_combine forms
+// the counts afterwards (a kernel boundary, rather than a device-wide fence
+// in every workgroup, makes the atomics of all workgroups visible to it).
+constexpr uint32_t kA4Chunk = kWave;   // 4-node hyperedges per wavefront item
+
+struct ExactArgs {
+  View v;
+  uint64_t n2, n3, n4;
+  const uint8_t* lut;
+  unsigned long long* hist;
+};
+
+// Order 4: items [0, n2) are the pairs of G2 (case (c)), [n2, n2 + n3) the
+// 3-node hyperedges (case (b)), then chunks of kA4Chunk 4-node hyperedges
+// (case (a)).  Dynamic LDS holds b4_set_words(W) words per wavefront.
+__global__ void __launch_bounds__(kThreads) k_exact4_bits(ExactArgs a) {
+  __shared__ uint8_t lut[2048];
+  __shared__ unsigned long long h_main[256], h_sub[256], h_g2[256];
+  __shared__ uint32_t ylist[kWavesPerBlock][kWave];
+  extern __shared__ uint32_t b4_sets[];
+  load_lut(lut, a.lut, 2048);
+  h_main[threadIdx.x] = 0;
+  h_sub[threadIdx.x] = 0;
+  h_g2[threadIdx.x] = 0;
+  __syncthreads();
+  const View& v = a.v;
+  const int wv = threadIdx.x / kWave;
+  const uint32_t lane = threadIdx.x & (kWave - 1);
+  uint32_t* sets = b4_sets + wv * b4_set_words(v.W);
+  const C4Lanes L = c4_lanes(v.W);
+  C4Acc acc;
+  c4_zero(acc);
+  const uint64_t n23 = a.n2 + a.n3;
+  const uint64_t items = n23 + (a.n4 + kA4Chunk - 1) / kA4Chunk;
+  const uint64_t n_waves = uint64_t(gridDim.x) * kWavesPerBlock;
+  for (uint64_t i = uint64_t(blockIdx.x) * kWavesPerBlock + wv; i < items; i += n_waves) {
+    if (i < a.n2) {
+      c4_bits_item(v, v.e2[2 * i], v.e2[2 * i + 1], L, ylist[wv], acc, lut, h_g2);
+    } else if (i < n23) {
+      b4_item(v, i - a.n2, sets, lut, h_main, h_sub);
+    } else {
+      const uint64_t e = (i - n23) * kA4Chunk + lane;
+      if (e < a.n4)
+        count_class(lut, h_main, h_sub, a4_pattern(v, v.e4[4 * e], v.e4[4 * e + 1], v.e4[4 * e + 2], v.e4[4 * e + 3]),
+                    kPairBits4);
+    }
+  }
+  c4_flush(acc, lut, h_g2);
+  __syncthreads();
+  flush(h_main, a.hist + kMain, 256);
+  flush(h_sub, a.hist + kSub, 256);
+  flush(h_g2, a.hist + kG2, 256);
+}
+
+// Order 3: thread items [0, n2 * W) are the (pair, word) tasks of case (c),
+// then one per 3-node hyperedge (case (a)).
+__global__ void __launch_bounds__(kThreads) k_exact3_bits(ExactArgs a) {
+  __shared__ uint8_t lut[16];
+  __shared__ unsigned long long h_main[256], h_sub[256], h_g2[256];
+  load_lut(lut, a.lut, 16);
+  h_main[threadIdx.x] = 0;
+  h_sub[threadIdx.x] = 0;
+  h_g2[threadIdx.x] = 0;
+  __syncthreads();
+  const View& v = a.v;
+  C3Acc acc{0, 0, 0};
+  const uint64_t tasks = a.n2 * v.W;
+  const uint64_t items = tasks + a.n3;
+  for (uint64_t t = uint64_t(blockIdx.x) * kThreads + threadIdx.x; t < items; t += uint64_t(gridDim.x) * kThreads) {
+    if (t < tasks) {
+      const uint64_t i = t / v.W;
+      c3_bits_word(v, v.e2[2 * i], v.e2[2 * i + 1], uint32_t(t % v.W), acc);
+    } else {
+      const uint64_t i = t - tasks;
+      count_class(lut, h_main, h_sub, a3_pattern(v, v.e3[3 * i], v.e3[3 * i + 1], v.e3[3 * i + 2]), kPairBits3);
+    }
+  }
+  c3_flush(acc, lut, h_g2);
+  __syncthreads();
+  flush(h_main, a.hist + kMain, 256);
+  flush(h_sub, a.hist + kSub, 256);
+  flush(h_g2, a.hist + kG2, 256);
 }
 
 // Counting kernels keep per-class counters in LDS and flush them once per
@@ -128,11 +167,37 @@ __global__ void k_combine(const unsigned long long* __restrict__ hist, int n_cla
 // keeps those flushes (global atomics on a few hundred addresses) rare.
 constexpr unsigned kCountGrid = 512;
 
-unsigned grid_waves(uint64_t items, unsigned cap = kCountGrid) {
-  uint64_t g = (items + kWavesPerBlock - 1) / kWavesPerBlock;
-  if (g < 1) g = 1;
-  if (g > cap) g = cap;
-  return unsigned(g);
+// Workgroups of a fused counting launch: no more than are resident at once
+// (with `lds` bytes of dynamic LDS each), and no more than the items need.
+unsigned fused_grid(const void* kernel, size_t lds, uint64_t items, uint64_t per_block) {
+  struct Key {
+    const void* kernel;
+    size_t lds;
+    int dev;
+    bool operator<(const Key& o) const {
+      return std::tie(kernel, lds, dev) < std::tie(o.kernel, o.lds, o.dev);
+    }
+  };
+  static std::mutex mu;
+  static std::map<Key, uint64_t> resident_of;
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  uint64_t resident = 0;
+  {
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = resident_of.find(Key{kernel, lds, dev});
+    if (it != resident_of.end()) resident = it->second;
+  }
+  if (!resident) {
+    int cus = 256, per_cu = 1;
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kThreads, lds) != hipSuccess || per_cu < 1)
+      per_cu = 1;
+    resident = uint64_t(cus > 0 ? cus : 256) * uint64_t(per_cu);
+    std::lock_guard<std::mutex> lock(mu);
+    resident_of[Key{kernel, lds, dev}] = resident;
+  }
+  return unsigned(std::max<uint64_t>(1, std::min<uint64_t>(resident, (items + per_block - 1) / per_block)));
 }
 unsigned grid_threads(uint64_t items, unsigned cap = kCountGrid, unsigned per_block = kThreads) {
   uint64_t g = (items + per_block - 1) / per_block;
@@ -150,39 +215,56 @@ int count_exact_impl(const hm_graph* H, int k, int64_t* counts, hipStream_t st) 
   ClassMask pairs_only{{0, 0, 0, 0}};
   for (int c = 0; c < t.n_classes[k]; ++c)
     if (t.maxcard[k][c] == 2) pairs_only.w[c >> 6] |= 1ull << (c & 63);
-  HM_TRY(fill_u64(H->hist, 0, 4 * 256, st));
+  // H->hist is zero between calls; a call that fails part-way clears it on
+  // the next call
+  if (H->hist_dirty) {
+    HM_TRY(fill_u64(H->hist, 0, 4 * 256, st));
+    H->hist_dirty = false;
+  }
+  struct DirtyOnError {
+    const hm_graph* H;
+    bool ok = false;
+    ~DirtyOnError() {
+      if (!ok) H->hist_dirty = true;
+    }
+  } guard{H};
   const uint64_t n2 = H->n_by_size[2], n3 = H->n_by_size[3], n4 = H->n_by_size[4];
   const View v = view_of(H);
-  if (k == 4) {
-    if (n4) {
+  if (v.bits) {
+    ExactArgs a{};
+    a.v = v;
+    a.n2 = n2;
+    a.n3 = n3;
+    a.n4 = k == 4 ? n4 : 0;
+    a.lut = k == 4 ? lut4 : lut3;
+    a.hist = H->hist;
+    if (k == 4) {
+      const size_t lds = size_t(kWavesPerBlock) * b4_set_words(v.W) * 4;
+      const uint64_t items = n2 + n3 + (n4 + kA4Chunk - 1) / kA4Chunk;
+      const unsigned grid = fused_grid(reinterpret_cast<const void*>(k_exact4_bits), lds, items, kWavesPerBlock);
+      ProfileScope ps("k_exact4_bits", st);
+      k_exact4_bits<<<grid, kThreads, lds, st>>>(a);
+    } else {
+      const unsigned grid = fused_grid(reinterpret_cast<const void*>(k_exact3_bits), 0, n2 * v.W + n3, kThreads);
+      ProfileScope ps("k_exact3_bits", st);
+      k_exact3_bits<<<grid, kThreads, 0, st>>>(a);
+    }
+  } else {
+    if (k == 4 && n4) {
       ProfileScope ps("k_case_a4", st);
       k_case_a4<<<grid_threads(n4), kThreads, 0, st>>>(v, n4, lut4, H->hist);
     }
-    if (v.bits) {
-      if (n3) {
-        ProfileScope ps("k_case_b4_bits", st);
-        k_case_b4<<<grid_waves(n3), kThreads, 0, st>>>(v, n3, lut4, H->hist);
-      }
-      if (n2) {
-        ProfileScope ps("k_case_c4_bits", st);
-        k_case_c4_bits<<<grid_waves(n2), kThreads, 0, st>>>(v, n2, lut4, H->hist);
-      }
-    }
-  } else {
-    if (n3) {
+    if (k == 3 && n3) {
       ProfileScope ps("k_case_a3", st);
       k_case_a3<<<grid_threads(n3), kThreads, 0, st>>>(v, n3, lut3, H->hist);
     }
-    if (v.bits && n2) {
-      ProfileScope ps("k_case_c3_bits", st);
-      k_case_c3_bits<<<grid_threads(n2 * v.W), kThreads, 0, st>>>(v, n2, lut3, H->hist);
-    }
+    HM_HIP(hipGetLastError());
+    HM_TRY(count_sparse(H, k, st));
   }
-  HM_HIP(hipGetLastError());
-  if (!v.bits) HM_TRY(count_sparse(H, k, st));
   HM_HIP(hipGetLastError());
   k_combine<<<1, 256, 0, st>>>(H->hist, t.n_classes[k], pairs_only, counts);
   HM_HIP(hipGetLastError());
+  guard.ok = true;
   return HM_OK;
 }
 

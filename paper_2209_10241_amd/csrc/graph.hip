@@ -311,10 +311,10 @@ __global__ void __launch_bounds__(kTile) k_gather_tiles(const uint32_t* __restri
 
 // Up to eight fills in one launch.
 struct FillRegions {
-  void* ptr[8];
-  unsigned long long count[8];
-  unsigned long long value[8];
-  uint32_t wide[8];   // 1: 64-bit elements, 0: 32-bit
+  void* ptr[10];
+  unsigned long long count[10];
+  unsigned long long value[10];
+  uint32_t wide[10];   // 1: 64-bit elements, 0: 32-bit
   uint32_t n;
 };
 
@@ -606,6 +606,7 @@ int build(hm_graph* H, const uint32_t* members_in, const uint64_t* offsets_in, u
     add(H->hs3.slot, 2 * c3, kEmpty64, 1);
     add(H->hs4.slot, 2 * c4, kEmpty64, 1);
     add(H->sample_hist, 256 + 8, 0, 1);
+    add(H->hist, 4 * 256, 0, 1);
     add(deg2, N, 0, 0);
     add(deg3, N, 0, 0);
     add(deg4, N, 0, 0);

@@ -17,12 +17,8 @@
 namespace hm {
 
 constexpr uint32_t kMaxWordsB = kBitsetMaxNodes / 32;
-constexpr int kChunkWords = kWave;
-
-struct B4Scratch {
-  uint32_t sets[4][kMaxWordsB];      // T_ab, T_ac, T_bc, Q
-  uint32_t list[kChunkWords * 32];
-};
+// LDS words one wavefront needs for rows of W words: T_ab, T_ac, T_bc, Q
+__host__ __device__ constexpr uint32_t b4_set_words(uint32_t W) { return 4 * W; }
 
 __device__ inline void count_class(const uint8_t* lut, unsigned long long* h_main, unsigned long long* h_sub,
                                    uint32_t pattern, uint32_t pair_bits) {
@@ -107,31 +103,29 @@ __device__ void b4_edge_hash(uint32_t a, uint32_t b, uint32_t c, const uint32_t*
 }
 
 // Bit-row version, counting instead of listing.  The wavefront builds, in
-// LDS, bit sets of the nodes v with {a,b,v}, {a,c,v} or {b,c,v} a 3-node
-// hyperedge (T_ab, T_ac, T_bc, from the incident 3-node hyperedges of a and b)
-// and with e u {v} a 4-node hyperedge (Q, from those of a).  Any other v
-// leaves e the only hyperedge of size >= 3 in e u {v}, so those v are counted
-// per pairwise combination (av, bv, cv) with popcounts over the rows of a, b,
-// c; the nodes of the T sets outside Q are classified one by one.
+// LDS (sets: 4*W words), bit sets of the nodes v with {a,b,v}, {a,c,v} or
+// {b,c,v} a 3-node hyperedge (T_ab, T_ac, T_bc, from the incident 3-node
+// hyperedges of a and b) and with e u {v} a 4-node hyperedge (Q, from those
+// of a).  Any other v leaves e the only hyperedge of size >= 3 in e u {v}, so
+// those v are counted per pairwise combination (av, bv, cv) with popcounts
+// over the rows of a, b, c; each lane classifies the nodes of its words that
+// lie in a T set and outside Q one by one.
 template <bool OWN>
 __device__ void b4_edge_bits_count(uint32_t a, uint32_t b, uint32_t c, const uint32_t* __restrict__ e3,
                                    const uint32_t* __restrict__ e4, const uint32_t* __restrict__ i3_off,
                                    const uint32_t* __restrict__ i3_idx, const uint32_t* __restrict__ i4_off,
                                    const uint32_t* __restrict__ i4_idx, const uint32_t* __restrict__ bits,
-                                   uint32_t W, B4Scratch& sc, const uint8_t* lut, unsigned long long* h_main,
+                                   uint32_t W, uint32_t* sets, const uint8_t* lut, unsigned long long* h_main,
                                    unsigned long long* h_sub) {
   const int lane = threadIdx.x & (kWave - 1);
-  uint32_t* Tab = sc.sets[0];
-  uint32_t* Tac = sc.sets[1];
-  uint32_t* Tbc = sc.sets[2];
-  uint32_t* Q = sc.sets[3];
-  uint32_t* list = sc.list;
+  uint32_t* Tab = sets;
+  uint32_t* Tac = sets + W;
+  uint32_t* Tbc = sets + 2 * W;
+  uint32_t* Q = sets + 3 * W;
   const uint32_t* Ra = bits + uint64_t(a) * W;
   const uint32_t* Rb = bits + uint64_t(b) * W;
   const uint32_t* Rc = bits + uint64_t(c) * W;
-  for (uint32_t w = lane; w < W; w += kWave) {
-    Tab[w] = 0; Tac[w] = 0; Tbc[w] = 0; Q[w] = 0;
-  }
+  for (uint32_t w = lane; w < 4 * W; w += kWave) sets[w] = 0;
   wave_sync();
   // 3-node hyperedges sharing two nodes with e
   const uint32_t pa = i3_off[a], la = i3_off[a + 1] - pa;
@@ -160,15 +154,16 @@ __device__ void b4_edge_bits_count(uint32_t a, uint32_t b, uint32_t c, const uin
   const uint32_t pab = (Ra[b >> 5] >> (b & 31)) & 1u, pac = (Ra[c >> 5] >> (c & 31)) & 1u,
                  pbc = (Rb[c >> 5] >> (c & 31)) & 1u;
   const uint32_t base_p = pab | (pac << 1) | (pbc << 2) | (1u << 3);
-  // the ordinary fourth nodes, per combination
   uint32_t n1 = 0, n2 = 0, n3 = 0, n4 = 0, n5 = 0, n6 = 0, n7 = 0;
   for (uint32_t w = lane; w < W; w += kWave) {
     const uint32_t ra = Ra[w], rb = Rb[w], rc = Rc[w];
-    uint32_t excl = Tab[w] | Tac[w] | Tbc[w] | Q[w];
-    if ((a >> 5) == w) excl |= 1u << (a & 31);
-    if ((b >> 5) == w) excl |= 1u << (b & 31);
-    if ((c >> 5) == w) excl |= 1u << (c & 31);
-    const uint32_t m = (ra | rb | rc) & ~excl;
+    const uint32_t tab_w = Tab[w], tac_w = Tac[w], tbc_w = Tbc[w], q_w = Q[w];
+    uint32_t self = 0;
+    if ((a >> 5) == w) self |= 1u << (a & 31);
+    if ((b >> 5) == w) self |= 1u << (b & 31);
+    if ((c >> 5) == w) self |= 1u << (c & 31);
+    // the ordinary fourth nodes, per combination
+    const uint32_t m = (ra | rb | rc) & ~(tab_w | tac_w | tbc_w | q_w | self);
     n1 += __popc(m & ra & ~rb & ~rc);
     n2 += __popc(m & ~ra & rb & ~rc);
     n3 += __popc(m & ra & rb & ~rc);
@@ -176,6 +171,19 @@ __device__ void b4_edge_bits_count(uint32_t a, uint32_t b, uint32_t c, const uin
     n5 += __popc(m & ra & ~rb & rc);
     n6 += __popc(m & ~ra & rb & rc);
     n7 += __popc(m & ra & rb & rc);
+    // the fourth nodes on another 3-node hyperedge (not on a 4-node one)
+    uint32_t cw = (tab_w | tac_w | tbc_w) & ~(q_w | self);
+    while (cw) {
+      const uint32_t vb = __ffs(cw) - 1;
+      cw &= cw - 1;
+      const uint32_t v = (w << 5) | vb;
+      const uint32_t tab = (tab_w >> vb) & 1u, tac = (tac_w >> vb) & 1u, tbc = (tbc_w >> vb) & 1u;
+      if (OWN && ((tab && v < c) || (tac && v < b) || (tbc && v < a))) continue;   // an earlier 3-node hyperedge
+      const uint32_t qa = (ra >> vb) & 1u, qb = (rb >> vb) & 1u, qc = (rc >> vb) & 1u;
+      // local positions a=0, b=1, c=2, v=3
+      const uint32_t pt = base_p | (qa << 4) | (qb << 5) | (tab << 6) | (qc << 7) | (tac << 8) | (tbc << 9);
+      count_class(lut, h_main, h_sub, pt, kPairBits4);
+    }
   }
   uint32_t n[8];
   n[1] = n1; n[2] = n2; n[3] = n3; n[4] = n4; n[5] = n5; n[6] = n6; n[7] = n7;
@@ -196,37 +204,7 @@ __device__ void b4_edge_bits_count(uint32_t a, uint32_t b, uint32_t c, const uin
       }
     }
   }
-  // the fourth nodes on another 3-node hyperedge (not on a 4-node one), one by one
-  for (uint32_t w0 = 0; w0 < W; w0 += kChunkWords) {
-    const uint32_t w = w0 + lane;
-    uint32_t cw = 0;
-    if (w < W) {
-      cw = (Tab[w] | Tac[w] | Tbc[w]) & ~Q[w];
-      if ((a >> 5) == w) cw &= ~(1u << (a & 31));
-      if ((b >> 5) == w) cw &= ~(1u << (b & 31));
-      if ((c >> 5) == w) cw &= ~(1u << (c & 31));
-    }
-    uint32_t total;
-    uint32_t pos = wave_exclusive_scan(__popc(cw), &total);
-    if (total == 0) continue;   // wave-uniform
-    while (cw) {
-      const uint32_t bit = __ffs(cw) - 1;
-      cw &= cw - 1;
-      list[pos++] = (w << 5) | bit;
-    }
-    wave_sync();
-    for (uint32_t t = lane; t < total; t += kWave) {
-      const uint32_t v = list[t];
-      const uint32_t vw = v >> 5, vb = v & 31;
-      const uint32_t tab = (Tab[vw] >> vb) & 1u, tac = (Tac[vw] >> vb) & 1u, tbc = (Tbc[vw] >> vb) & 1u;
-      if (OWN && ((tab && v < c) || (tac && v < b) || (tbc && v < a))) continue;   // an earlier 3-node hyperedge
-      const uint32_t qa = (Ra[vw] >> vb) & 1u, qb = (Rb[vw] >> vb) & 1u, qc = (Rc[vw] >> vb) & 1u;
-      // local positions a=0, b=1, c=2, v=3
-      const uint32_t pt = base_p | (qa << 4) | (qb << 5) | (tab << 6) | (qc << 7) | (tac << 8) | (tbc << 9);
-      count_class(lut, h_main, h_sub, pt, kPairBits4);
-    }
-    wave_sync();
-  }
+  wave_sync();   // the sets are rewritten by the wavefront's next 3-node hyperedge
 }
 
 }  // namespace hm

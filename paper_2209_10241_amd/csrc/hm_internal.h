@@ -233,8 +233,11 @@ struct hm_graph {
   uint32_t* bits = nullptr;
   uint32_t words = 0;
 
-  // histogram scratch, reused by the counting calls (serialised per graph)
+  // histogram scratch, reused by the counting calls (serialised per graph):
+  // main, sub and G2 regions of 256 counters (the fourth 256 unused); zero
+  // between calls (hist_dirty: a call failed part-way and left it unknown)
   unsigned long long* hist = nullptr;      // 4 x 256 counters
+  mutable bool hist_dirty = false;
   // pairs inside 3-node hyperedges, sorted ((x << 32) | y), with the position
   // of their hyperedge in e3; built on first use without bit rows
   unsigned long long* pl_keys = nullptr;
@@ -248,8 +251,8 @@ struct hm_graph {
   // triangles, 4-cliques and 4-cycles through it; over its common neighbours
   // x: sum of t_{ux}, sum of t_{wx}, sum of deg x
   unsigned long long* es = nullptr;
-  // raw counters (256) and finished-workgroup ticket of the sampled counting
-  // calls; zero between calls
+  // raw counters (256) of the sampled counting calls, then ([257], [258])
+  // the tail and head of their work queue; zero between calls
   unsigned long long* sample_hist = nullptr;
   // buffers and captured HIP graph of the batched null-model pipeline
   hm::NullPlan* null_plan = nullptr;

@@ -87,11 +87,11 @@ __device__ inline uint32_t a3_pattern(const View& v, uint32_t a, uint32_t b, uin
 }
 
 // (b) at order 4 for the 3-node hyperedge at position i of v.e3
-__device__ inline void b4_item(const View& v, uint64_t i, B4Scratch* sc, const uint8_t* lut, unsigned long long* h_main,
+__device__ inline void b4_item(const View& v, uint64_t i, uint32_t* sets, const uint8_t* lut, unsigned long long* h_main,
                                unsigned long long* h_sub) {
   const uint32_t a = v.e3[3 * i], b = v.e3[3 * i + 1], c = v.e3[3 * i + 2];
   if (v.bits)
-    b4_edge_bits_count<true>(a, b, c, v.e3, v.e4, v.i3_off, v.i3_idx, v.i4_off, v.i4_idx, v.bits, v.W, *sc, lut,
+    b4_edge_bits_count<true>(a, b, c, v.e3, v.e4, v.i3_off, v.i3_idx, v.i4_off, v.i4_idx, v.bits, v.W, sets, lut,
                              h_main, h_sub);
   else
     b4_edge_hash<true>(a, b, c, v.e3, v.g2_off, v.g2_adj, v.i3_off, v.i3_idx, v.hs2, v.hs3, v.hs4, lut, h_main, h_sub);
@@ -107,15 +107,22 @@ __device__ inline void b4_item(const View& v, uint64_t i, B4Scratch* sc, const u
 // W lanes, lane (g, w) owning word w of every y its group takes, so the words
 // of r and x and the masks that depend only on r are loaded once per pair;
 // wider rows loop over words.  Each word adds popcounts of the candidate z it
-// holds, split by the adjacency of z to x and y.
-// Named scalars (no arrays) keep every counter in registers.
+// holds, split by the adjacency of z to x and y.  The y of a batch are
+// ordered with those not adjacent to x first, so that x~y is fixed within
+// each of the two inner loops.
+// Named scalars (no arrays) keep every counter in registers.  Counters are
+// 32-bit: one pair adds at most 32 * 4 * 8192 < 2^20 to a lane's counter, so
+// flushing every kC4FlushItems pairs keeps them below 2^31.
+constexpr uint32_t kC4FlushItems = 2048;
+
 struct C4Acc {
   // |A| = 3, by (x~y, x~z, y~z)
-  unsigned long long a000, a001, a010, a011, a100, a101, a110, a111;
+  uint32_t a000, a001, a010, a011, a100, a101, a110, a111;
   // |A| = 2, by x~y and z adjacent to both / x only / y only
-  unsigned long long b0b, b0x, b0y, b1b, b1x, b1y;
+  uint32_t b0b, b0x, b0y, b1b, b1x, b1y;
   // |A| = 1
-  unsigned long long paw, star, path;
+  uint32_t paw, star, path;
+  uint32_t items;   // pairs since the last flush
 };
 
 struct C4Lanes {
@@ -139,23 +146,40 @@ __device__ inline void c4_zero(C4Acc& a) {
   a.a000 = a.a001 = a.a010 = a.a011 = a.a100 = a.a101 = a.a110 = a.a111 = 0;
   a.b0b = a.b0x = a.b0y = a.b1b = a.b1x = a.b1y = 0;
   a.paw = a.star = a.path = 0;
+  a.items = 0;
 }
 
-__device__ inline void c4_word(uint32_t Nr, uint32_t Nx, uint32_t Ny, uint32_t gy, uint32_t wr, bool xy, C4Acc& a) {
+// one word of z candidates for a y with x~y = XY
+template <bool XY>
+__device__ inline void c4_word(uint32_t Nr, uint32_t Nx, uint32_t Ny, uint32_t gy, uint32_t wr, C4Acc& a) {
   const uint32_t z3 = Nr & gy;
-  const uint32_t z3x = z3 & Nx, z3n = z3 & ~Nx;
-  const uint32_t c11 = __popc(z3x & Ny), c10 = __popc(z3x & ~Ny), c01 = __popc(z3n & Ny), c00 = __popc(z3n & ~Ny);
   const uint32_t z2 = wr & (Nx | Ny);
-  const uint32_t b2 = __popc(z2 & Nx & Ny), bx = __popc(z2 & Nx & ~Ny), by = __popc(z2 & ~Nx & Ny);
-  const uint32_t m1 = xy ? ~0u : 0u, m0 = ~m1;
-  a.a011 += c11 & m0; a.a010 += c10 & m0; a.a001 += c01 & m0; a.a000 += c00 & m0;
-  a.a111 += c11 & m1; a.a110 += c10 & m1; a.a101 += c01 & m1; a.a100 += c00 & m1;
-  a.b0b += b2 & m0; a.b0x += bx & m0; a.b0y += by & m0;
-  a.b1b += b2 & m1; a.b1x += bx & m1; a.b1y += by & m1;
+  if (XY) {
+    a.a111 += __popc(z3 & Nx & Ny);
+    a.a110 += __popc(z3 & Nx & ~Ny);
+    a.a101 += __popc(z3 & ~Nx & Ny);
+    a.a100 += __popc(z3 & ~Nx & ~Ny);
+    a.b1b += __popc(z2 & Nx & Ny);
+    a.b1x += __popc(z2 & Nx & ~Ny);
+    a.b1y += __popc(z2 & ~Nx & Ny);
+  } else {
+    a.a011 += __popc(z3 & Nx & Ny);
+    a.a010 += __popc(z3 & Nx & ~Ny);
+    a.a001 += __popc(z3 & ~Nx & Ny);
+    a.a000 += __popc(z3 & ~Nx & ~Ny);
+    a.b0b += __popc(z2 & Nx & Ny);
+    a.b0x += __popc(z2 & Nx & ~Ny);
+    a.b0y += __popc(z2 & ~Nx & Ny);
+  }
 }
 
-// ys: 64 words of wavefront-private LDS
-__device__ inline void c4_bits_item(const View& v, uint32_t r, uint32_t x, const C4Lanes& L, uint32_t* ys, C4Acc& acc) {
+__device__ inline void c4_flush(const C4Acc& a, const uint8_t* lut, unsigned long long* h_g2);
+
+// ys: 64 words of wavefront-private LDS.  Every lane of the wavefront calls
+// this; the counters go to h_g2 (LDS) every kC4FlushItems pairs and at
+// c4_flush.
+__device__ inline void c4_bits_item(const View& v, uint32_t r, uint32_t x, const C4Lanes& L, uint32_t* ys, C4Acc& acc,
+                                    const uint8_t* lut, unsigned long long* h_g2) {
   const int lane = threadIdx.x & (kWave - 1);
   const uint32_t W = v.W;
   const uint32_t* Rr = v.bits + uint64_t(r) * W;
@@ -164,20 +188,28 @@ __device__ inline void c4_bits_item(const View& v, uint32_t r, uint32_t x, const
   const uint32_t p = upper_bound(v.g2_adj, v.g2_off[r], re, x);
   const uint32_t xe = v.g2_off[x + 1];
   const uint32_t q = upper_bound(v.g2_adj, v.g2_off[x], xe, r);
+  const unsigned long long below = (1ull << lane) - 1ull;
   // |A| = 3 and |A| = 2: y over the neighbours of r above x, 64 at a time
   for (uint32_t base = p; base < re; base += kWave) {
     const uint32_t cnt = min(uint32_t(kWave), re - base);
-    if (uint32_t(lane) < cnt) ys[lane] = v.g2_adj[base + lane];
+    const bool in = uint32_t(lane) < cnt;
+    const uint32_t y0 = in ? v.g2_adj[base + lane] : 0u;
+    const bool xy0 = in && ((Rx[y0 >> 5] >> (y0 & 31)) & 1u);
+    const unsigned long long m0 = __ballot(in && !xy0), m1 = __ballot(xy0);
+    const uint32_t n0 = uint32_t(__popcll(m0));
+    if (in) ys[xy0 ? n0 + uint32_t(__popcll(m1 & below)) : uint32_t(__popcll(m0 & below))] = y0;
     wave_sync();
     if (L.on)
       for (uint32_t w = L.w0; w < W; w += L.wstep) {
         const uint32_t Nr = Rr[w], Nx = Rx[w];
         const uint32_t wr = ~Nr & mask_gt(r, w) & mask_below(v.N, w);
-        for (uint32_t j = L.g; j < cnt; j += L.G) {
+        for (uint32_t j = L.g; j < n0; j += L.G) {
           const uint32_t y = ys[j];
-          const uint32_t Ny = v.bits[uint64_t(y) * W + w];
-          const bool xy = (Rx[y >> 5] >> (y & 31)) & 1u;
-          c4_word(Nr, Nx, Ny, mask_gt(y, w), wr, xy, acc);
+          c4_word<false>(Nr, Nx, v.bits[uint64_t(y) * W + w], mask_gt(y, w), wr, acc);
+        }
+        for (uint32_t j = n0 + L.g; j < cnt; j += L.G) {
+          const uint32_t y = ys[j];
+          c4_word<true>(Nr, Nx, v.bits[uint64_t(y) * W + w], mask_gt(y, w), wr, acc);
         }
       }
     wave_sync();
@@ -189,31 +221,35 @@ __device__ inline void c4_bits_item(const View& v, uint32_t r, uint32_t x, const
     const bool keep = in && !((Rr[y0 >> 5] >> (y0 & 31)) & 1u);
     const unsigned long long mk = __ballot(keep);
     const uint32_t cnt = uint32_t(__popcll(mk));
-    if (keep) ys[__popcll(mk & ((1ull << lane) - 1ull))] = y0;
+    if (keep) ys[__popcll(mk & below)] = y0;
     wave_sync();
     if (L.on)
       for (uint32_t w = L.w0; w < W; w += L.wstep) {
         const uint32_t Nr = Rr[w], Nx = Rx[w];
         const uint32_t wr = ~Nr & mask_gt(r, w) & mask_below(v.N, w);
         const uint32_t nxw = Nx & wr;
+        const uint32_t pw = wr & ~Nx;
         for (uint32_t j = L.g; j < cnt; j += L.G) {
           const uint32_t y = ys[j];
           const uint32_t Ny = v.bits[uint64_t(y) * W + w];
           const uint32_t zz = nxw & mask_gt(y, w);
           acc.paw += __popc(zz & Ny);
           acc.star += __popc(zz & ~Ny);
-          acc.path += __popc(Ny & wr & ~Nx);
+          acc.path += __popc(Ny & pw);
         }
       }
     wave_sync();
+  }
+  if (++acc.items == kC4FlushItems) {
+    c4_flush(acc, lut, h_g2);
+    c4_zero(acc);
   }
 }
 
 // Reduce the accumulators over the wavefront and add them to the G2-shape
 // counters h_g2 (lane 0 adds); every lane of the wavefront must call this.
-__device__ inline void c4_emit(unsigned long long value, uint32_t pattern, const uint8_t* lut,
-                               unsigned long long* h_g2) {
-  const unsigned long long sum = wave_sum(value);
+__device__ inline void c4_emit(uint32_t value, uint32_t pattern, const uint8_t* lut, unsigned long long* h_g2) {
+  const unsigned long long sum = wave_sum((unsigned long long)value);
   if ((threadIdx.x & (kWave - 1)) == 0 && sum) atomicAdd(&h_g2[lut[pattern]], sum);
 }
 

@@ -568,7 +568,7 @@ __global__ void __launch_bounds__(kThreads) k_null_count(BatchView b, uint32_t R
                                                          unsigned long long* __restrict__ hist_all) {
   __shared__ uint8_t lut[2048];
   __shared__ unsigned long long wh[kWavesPerBlock][512];
-  __shared__ B4Scratch scratch[kWavesPerBlock];
+  extern __shared__ uint32_t b4_sets[];   // b4_set_words(W) words per wavefront
   __shared__ uint32_t ylist[kWavesPerBlock][kWave];
   load_lut(lut, lut_g, k == 4 ? 2048 : 16);
   __syncthreads();
@@ -598,7 +598,7 @@ __global__ void __launch_bounds__(kThreads) k_null_count(BatchView b, uint32_t R
     if (ph == 0) {
       const uint32_t n = b.base3[c + 1] - b.base3[c];
       const uint32_t last = min(n, first + ch.per_tile[0]);
-      for (uint32_t j = first; j < last; ++j) b4_item(v, b.base3[c] + j, &scratch[wv], lut, h_main, h_sub);
+      for (uint32_t j = first; j < last; ++j) b4_item(v, b.base3[c] + j, b4_sets + wv * b4_set_words(b.W), lut, h_main, h_sub);
     } else if (ph == 1) {
       const uint32_t n = b.base2[c + 1] - b.base2[c];
       const uint32_t last = min(n, first + ch.per_tile[1]);
@@ -608,7 +608,7 @@ __global__ void __launch_bounds__(kThreads) k_null_count(BatchView b, uint32_t R
           c4_zero(acc);
           for (uint32_t j = first; j < last; ++j) {
             const uint64_t q = b.base2[c] + j;
-            c4_bits_item(v, b.e2[2 * q], b.e2[2 * q + 1], L, ylist[wv], acc);
+            c4_bits_item(v, b.e2[2 * q], b.e2[2 * q + 1], L, ylist[wv], acc, lut, hc + kG2);
           }
           c4_flush(acc, lut, hc + kG2);
         } else {
@@ -949,14 +949,14 @@ int enqueue_ingest(const hm_graph* H, NullPlan& P, hipStream_t st) {
   return HM_OK;
 }
 
-unsigned persistent_grid() {
-  static unsigned g = 0;
-  if (!g) {
-    int dev = 0, cus = 256;
-    if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    g = unsigned(cus > 0 ? cus : 256) * 2;
-  }
-  return g;
+// Workgroups of the persistent counting kernel: as many as are resident at
+// once with `lds` bytes of dynamic LDS each, at most four per CU.
+unsigned persistent_grid(size_t lds) {
+  int dev = 0, cus = 256, per_cu = 2;
+  if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_null_count, kThreads, lds) != hipSuccess) per_cu = 2;
+  per_cu = per_cu < 1 ? 1 : (per_cu > 4 ? 4 : per_cu);
+  return unsigned(cus > 0 ? cus : 256) * unsigned(per_cu);
 }
 
 int enqueue_count(const hm_graph* H, NullPlan& P, const Chunks& ch, hipStream_t st) {
@@ -969,7 +969,8 @@ int enqueue_count(const hm_graph* H, NullPlan& P, const Chunks& ch, hipStream_t 
   HM_TRY(scan_u32_ws(P.tile_counts, P.tile_prefix, 3ull * R, P.tile_prefix + 3ull * R, P.scan_ws, st));
   HM_TRY(fill_u64(P.hist_all, 0, uint64_t(R) * kHistWords, st));
   HM_TRY(fill_u32(P.tile_counter, 0, 1, st));
-  k_null_count<<<persistent_grid(), kThreads, 0, st>>>(bv, R, P.k, P.tile_prefix, P.tile_counter, ch,
+  const size_t lds = (P.k == 4 && bv.bits) ? size_t(kWavesPerBlock) * b4_set_words(bv.W) * 4 : 0;
+  k_null_count<<<persistent_grid(lds), kThreads, lds, st>>>(bv, R, P.k, P.tile_prefix, P.tile_counter, ch,
                                                        P.k == 4 ? lut4 : lut3, P.hist_all);
   HM_HIP(hipGetLastError());
   const ClassTables& t = class_tables();

@@ -120,7 +120,7 @@ __device__ __forceinline__ void j3_exceptions(const View& v, const PairLinks& pl
 
 template <bool BITS>
 __device__ void sample_j3_k4(const View& v, const PairLinks& pl, const Queue& q, const Draws& d, uint32_t part,
-                             uint32_t n_parts, B4Scratch* scratch, const uint8_t* lut, unsigned long long* h_lds,
+                             uint32_t n_parts, uint32_t* sets, const uint8_t* lut, unsigned long long* h_lds,
                              unsigned long long* rows) {
   const int wv = threadIdx.x / kWave;
   const uint32_t lane = threadIdx.x & (kWave - 1);
@@ -130,7 +130,7 @@ __device__ void sample_j3_k4(const View& v, const PairLinks& pl, const Queue& q,
     const uint32_t a = v.e3[3 * i], b = v.e3[3 * i + 1], c = v.e3[3 * i + 2];
     unsigned long long* h = row_or(rows, s, h_lds);
     if constexpr (BITS) {
-      b4_edge_bits_count<false>(a, b, c, v.e3, v.e4, v.i3_off, v.i3_idx, v.i4_off, v.i4_idx, v.bits, v.W, scratch[wv],
+      b4_edge_bits_count<false>(a, b, c, v.e3, v.e4, v.i3_off, v.i3_idx, v.i4_off, v.i4_idx, v.bits, v.W, sets + wv * b4_set_words(v.W),
                                 lut, h, nullptr);
     } else {
       const B4Ctx x = b4_ctx(v, pl, a, b, c);
@@ -807,7 +807,6 @@ struct SampledArgs {
   uint32_t blocks[5];            // workgroups of strata 2, 3, 4 (in this order in the grid)
   unsigned long long* rows[5];   // per-sample rows (256 counters) of each stratum, or null
   unsigned long long* hist;      // 256 raw counters, zero on entry; left zero after scaling
-  unsigned int* ticket;          // workgroups done; zero on entry and left zero
   float* est;                    // null: no scaling (row mode)
   int64_t* raw;
   int n_classes;
@@ -820,7 +819,7 @@ struct SampledLds {
 template <>
 struct SampledLds<4, true> {
   union {
-    B4Scratch b4[kWavesPerBlock];
+    uint32_t b4[kWavesPerBlock * b4_set_words(kMaxWordsB)];
     J2Lds j2;
   };
 };
@@ -829,20 +828,14 @@ struct SampledLds<4, false> {
   J2SparseLds j2;
 };
 
-// After a workgroup's counts reached a.hist: the last workgroup of the launch
-// scales them (Algorithm 4's correction: est_m = raw_m * |E_mc| / (S_mc *
-// countmax_m) in fp64, rounded once to fp32, 0 when the stratum was not
-// sampled) and clears a.hist, the ticket and the queue counters.
-__device__ void finish_sampled(const SampledArgs& a, const ScaleArgs& sc) {
-  __shared__ uint32_t last;
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) last = atomicAdd(a.ticket, 1u) == gridDim.x - 1;
-  __syncthreads();
-  if (!last) return;
-  __threadfence();
+// After the sampler (and its queue's drain): scale the raw counts in a.hist
+// (Algorithm 4's correction: est_m = raw_m * |E_mc| / (S_mc * countmax_m) in
+// fp64, rounded once to fp32, 0 when the stratum was not sampled) and clear
+// a.hist and the queue counters.  One workgroup of 256; the kernel boundary
+// makes the atomics of every workgroup of the sampler visible to it.
+__global__ void __launch_bounds__(kThreads) k_finish_sampled(SampledArgs a, ScaleArgs sc) {
   const int c = threadIdx.x;
-  const unsigned long long r = __hip_atomic_load(a.hist + c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  const unsigned long long r = a.hist[c];
   if (a.est && c < a.n_classes) {
     const int j = sc.maxcard[c];
     double e = 0.0;
@@ -852,22 +845,17 @@ __device__ void finish_sampled(const SampledArgs& a, const ScaleArgs& sc) {
   }
   a.hist[c] = 0;
   if (c == 0) {
-    *a.ticket = 0;
-    if (a.q.job) {
-      *a.q.tail = 0;
-      *a.q.head = 0;
-    }
+    *a.q.tail = 0;
+    *a.q.head = 0;
   }
 }
 
 // Every stratum's samples in one launch.  The grid holds a.blocks[2]
 // workgroups for the sampled pairs, then a.blocks[3] for the 3-node and
 // a.blocks[4] for the 4-node hyperedges.  Each workgroup adds its LDS counts to
-// a.hist; the last one to finish scales them (Algorithm 4's correction:
-// est_m = raw_m * |E_mc| / (S_mc * countmax_m) in fp64, rounded once to fp32,
-// 0 when the stratum was not sampled) and clears a.hist and a.ticket.
+// a.hist (k_finish_sampled scales them).
 template <int K, bool BITS>
-__global__ void __launch_bounds__(kThreads) k_sampled(SampledArgs a, ScaleArgs sc) {
+__global__ void __launch_bounds__(kThreads) k_sampled(SampledArgs a) {
   constexpr int kLut = K == 4 ? 2048 : 16;
   __shared__ uint8_t lut[kLut];
   __shared__ unsigned long long h_lds[256];
@@ -896,13 +884,10 @@ __global__ void __launch_bounds__(kThreads) k_sampled(SampledArgs a, ScaleArgs s
   }
   __syncthreads();
   flush(h_lds, a.hist, 256);
-  if (a.q.job) return;   // the queue's drain finishes the call
-  finish_sampled(a, sc);
 }
 
-// Drain the work queue that k_sampled filled (without bit rows), then finish
-// the call as k_sampled does otherwise.
-__global__ void __launch_bounds__(kThreads) k_sampled_drain(SampledArgs a, ScaleArgs sc) {
+// Drain the work queue that k_sampled filled (without bit rows).
+__global__ void __launch_bounds__(kThreads) k_sampled_drain(SampledArgs a) {
   __shared__ uint8_t lut[2048];
   __shared__ unsigned long long h_lds[256];
   __shared__ J2SparseLds L;
@@ -944,7 +929,6 @@ __global__ void __launch_bounds__(kThreads) k_sampled_drain(SampledArgs a, Scale
   }
   __syncthreads();
   flush(h_lds, a.hist, 256);
-  finish_sampled(a, sc);
 }
 
 unsigned grid_for(uint64_t items, uint64_t per_block, unsigned cap = 512) {
@@ -1005,12 +989,11 @@ int launch_sampled(const hm_graph* H, int k, const uint32_t* const idx[5], const
     a.blocks[3] = blocks_for(a.d.S[3], kThreads, 256);
   }
   uint32_t grid = a.blocks[2] + a.blocks[3] + a.blocks[4];
-  if (grid == 0) {   // nothing sampled: one workgroup still scales (to zeros)
+  if (grid == 0) {   // nothing sampled: one idle workgroup
     a.blocks[2] = 1;
     grid = 1;
   }
   a.hist = H->sample_hist;
-  a.ticket = reinterpret_cast<unsigned int*>(H->sample_hist + 256);
   a.est = rows ? nullptr : est;
   a.raw = rows ? nullptr : raw;
   const ClassTables& t = class_tables();
@@ -1053,16 +1036,18 @@ int launch_sampled(const hm_graph* H, int k, const uint32_t* const idx[5], const
   }
   ProfileScope pscope("k_sampled", st);
   if (k == 4 && bits)
-    k_sampled<4, true><<<grid, kThreads, 0, st>>>(a, sc);
+    k_sampled<4, true><<<grid, kThreads, 0, st>>>(a);
   else if (k == 4)
-    k_sampled<4, false><<<grid, kThreads, 0, st>>>(a, sc);
+    k_sampled<4, false><<<grid, kThreads, 0, st>>>(a);
   else
-    k_sampled<3, false><<<grid, kThreads, 0, st>>>(a, sc);
+    k_sampled<3, false><<<grid, kThreads, 0, st>>>(a);
   HM_HIP(hipGetLastError());
   if (a.q.job) {
-    k_sampled_drain<<<1024, kThreads, 0, st>>>(a, sc);
+    k_sampled_drain<<<1024, kThreads, 0, st>>>(a);
     HM_HIP(hipGetLastError());
   }
+  k_finish_sampled<<<1, kThreads, 0, st>>>(a, sc);
+  HM_HIP(hipGetLastError());
   return HM_OK;
 }
 

@@ -103,6 +103,21 @@ def test_sparse_path_agrees_with_bit_rows(hm, scale):
         assert a.sum() > 0
 
 
+@pytest.mark.parametrize("bit_rows", [True, False], ids=["bits", "hash"])
+def test_repeated_calls_on_one_graph(hm, bit_rows):
+    """The counting scratch is left clear after every call: orders alternate on
+    one graph and every call matches the oracle."""
+    h = W.random_small(77, 50, 600, {2: 0.5, 3: 0.3, 4: 0.2}, allow_dups=True)
+    want = {k: core.count_exact(h, k) for k in (3, 4)}
+    hm.hm_set_option(hm.HM_OPT_BITSET_MAX_NODES, 8192 if bit_rows else 0)
+    try:
+        with hm.hm_graph_create(h.members, h.offsets, h.n_nodes) as g:
+            for k in (4, 4, 3, 4, 3, 3, 4):
+                assert np.array_equal(hm.count_exact(g, k).cpu().numpy(), want[k]), k
+    finally:
+        hm.hm_set_option(hm.HM_OPT_BITSET_MAX_NODES, 8192)
+
+
 def test_facetoface_order4_relabelled(hm):
     h = W.cfg1_facetoface_k4(0)
     perm = np.random.default_rng(5).permutation(h.n_nodes)
