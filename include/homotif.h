@@ -89,21 +89,30 @@ int hm_pattern_class(int k, uint32_t pattern, int* cls);
  * Section 3): validate, sort members, collapse repeated hyperedges, split by
  * size, hash every hyperedge of size 2..4 (Section 4.3, Fig. 3b) and build the
  * adjacency used by the enumeration.
- *   members  n_members = offsets[n_edges] node ids; offsets n_edges+1 values
- *   mem_kind HM_MEM_HOST or HM_MEM_DEVICE: where members and offsets live
- *   stream   hipStream_t for the build.  The call returns once the input has
- *            been validated and the sizes are known (hm_graph_stats is then
- *            exact); the rest of the build stays enqueued on the stream, so
- *            later calls on the same stream see the finished graph, and work
- *            on another stream must first wait for this one.  The caller's
- *            members/offsets buffers may be reused as soon as it returns.
- *   out      receives the handle
+ *   members   node ids; hyperedge i is members[offsets[i] .. offsets[i+1])
+ *   offsets   n_edges+1 values, offsets[0] = 0, non-decreasing
+ *   n_members number of entries of members (offsets[n_edges] <= n_members;
+ *             at most 2^32-1)
+ *   mem_kind  HM_MEM_HOST or HM_MEM_DEVICE: where members and offsets live
+ *   stream    hipStream_t for the build.  The call returns once the input
+ *             has been validated and the sizes are known (hm_graph_stats is
+ *             then exact); the rest of the build stays enqueued on the
+ *             stream, so later calls on the same stream see the finished
+ *             graph, and work on another stream must first wait for this
+ *             one.  The caller's members/offsets buffers may be reused as
+ *             soon as it returns.
+ *   out       receives the handle
  * Errors: HM_EINVAL for an empty hyperedge, a node id >= n_nodes, a node
- * repeated inside a hyperedge, non-monotone offsets or n_nodes = 0. */
-int hm_graph_create(const uint32_t* members, const uint64_t* offsets, uint64_t n_edges,
+ * repeated inside a hyperedge, offsets that do not start at 0, decrease or
+ * exceed n_members, or n_nodes = 0; HM_EUNSUPPORTED for n_members >= 2^32. */
+int hm_graph_create(const uint32_t* members, const uint64_t* offsets, uint64_t n_edges, uint64_t n_members,
                     uint32_t n_nodes, int mem_kind, void* stream, hm_graph** out);
 
-/* Release a graph handle (NULL is accepted). */
+/* Release a graph handle (NULL is accepted).  Does not wait for the device:
+ * when all work on the graph was enqueued on one stream its memory is reused
+ * only by work enqueued after this call; otherwise (several streams, or a
+ * null-model pipeline or learned proposal attached) the call first waits for
+ * the device to be idle. */
 int hm_graph_destroy(hm_graph* H);
 
 /* Host array of 10 values: n_nodes, unique hyperedges of size 2, 3, 4, unique

@@ -57,7 +57,7 @@ SIGNATURES = {
     "hm_num_classes": (_int, [_int]),
     "hm_class_info": (_int, [_int, _int, _vp, _vp, _vp]),
     "hm_pattern_class": (_int, [_int, _u32, _vp]),
-    "hm_graph_create": (_int, [_vp, _vp, _u64, _u32, _int, _vp, _vp]),
+    "hm_graph_create": (_int, [_vp, _vp, _u64, _u64, _u32, _int, _vp, _vp]),
     "hm_graph_destroy": (_int, [_vp]),
     "hm_graph_stats": (_int, [_vp, _vp]),
     "hm_graph_export": (_int, [_vp, _int, _vp]),
@@ -197,14 +197,15 @@ def hm_graph_create(members, offsets, n_nodes: int, stream=None) -> Graph:
         offsets = offsets.to(torch.int64).contiguous()
         n_edges = offsets.numel() - 1
         rc = lib().hm_graph_create(ctypes.c_void_p(members.data_ptr()), ctypes.c_void_p(offsets.data_ptr()),
-                                   n_edges, n_nodes, HM_MEM_DEVICE, _stream_ptr(stream), ctypes.byref(out))
+                                   n_edges, members.numel(), n_nodes, HM_MEM_DEVICE, _stream_ptr(stream),
+                                   ctypes.byref(out))
     else:
         m = np.ascontiguousarray(members, dtype=np.uint32)
         o = np.ascontiguousarray(offsets, dtype=np.uint64)
         n_edges = len(o) - 1
         st = _stream_ptr(stream) if _cuda_available() else ctypes.c_void_p(0)
         rc = lib().hm_graph_create(m.ctypes.data_as(ctypes.c_void_p), o.ctypes.data_as(ctypes.c_void_p),
-                                   n_edges, n_nodes, HM_MEM_HOST, st, ctypes.byref(out))
+                                   n_edges, len(m), n_nodes, HM_MEM_HOST, st, ctypes.byref(out))
     _check(rc)
     return Graph(out.value, n_nodes)
 

@@ -209,6 +209,7 @@ unsigned grid_threads(uint64_t items, unsigned cap = kCountGrid, unsigned per_bl
 }  // namespace
 
 int count_exact_impl(const hm_graph* H, int k, int64_t* counts, hipStream_t st) {
+  note_use(H, st);
   const uint8_t *lut4 = nullptr, *lut3 = nullptr;
   HM_TRY(device_luts(H->device, &lut4, &lut3));
   const ClassTables& t = class_tables();

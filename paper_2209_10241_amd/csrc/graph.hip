@@ -9,6 +9,7 @@
 // node count is small, and every node lists its incident 3- and 4-node
 // hyperedges: the neighbourhoods Algorithms 3 and 4 explore.
 #include <algorithm>
+#include <mutex>
 #include <vector>
 
 #include "hm_device.h"
@@ -39,16 +40,17 @@ __device__ inline unsigned long long tuple_hash(const uint32_t* m, uint32_t s) {
 }
 
 // One thread per input hyperedge: copy its members, sort them, check ids and
-// repeats, record its size and hash.
+// repeats, record its size and hash.  Offsets start at 0, never decrease and
+// stay within the n_members entries of members.
 __global__ void k_prepare(const uint32_t* __restrict__ members, const uint64_t* __restrict__ offsets,
-                          uint64_t n_edges, uint64_t nnz, uint32_t n_nodes, uint32_t* __restrict__ sm,
+                          uint64_t n_edges, uint64_t n_members, uint32_t n_nodes, uint32_t* __restrict__ sm,
                           uint32_t* __restrict__ size, unsigned long long* __restrict__ hash,
                           DevFlags* flags) {
   for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n_edges;
        i += uint64_t(gridDim.x) * blockDim.x) {
     const uint64_t b = offsets[i], e = offsets[i + 1];
     uint32_t err = 0;
-    if (e < b || e > nnz) {
+    if (e < b || e > n_members || (i == 0 && b != 0)) {
       err |= kErrOffsets;
       size[i] = 0;
       hash[i] = 0;
@@ -104,28 +106,35 @@ __device__ inline bool same_tuple(const uint32_t* sm, const uint64_t* off, const
   return true;
 }
 
-// Insert every hyperedge of size >= 2 into a table of edge indices; equal
-// tuples meet in one slot, which keeps the smallest index (first occurrence).
+// Insert every hyperedge of size >= 2 into a table whose slots hold
+// (tag << 32) | index, the tag being the high half of the hyperedge's hash;
+// equal tuples meet in one slot, which keeps the smallest index (first
+// occurrence).  slot_of[i] records the slot of hyperedge i.
 __global__ void k_dedup_insert(const uint32_t* __restrict__ sm, const uint64_t* __restrict__ off,
                                const uint32_t* __restrict__ size, const unsigned long long* __restrict__ hash,
-                               uint64_t n_edges, uint32_t* slots, unsigned long long mask) {
+                               uint64_t n_edges, unsigned long long* slots, unsigned long long mask,
+                               unsigned long long* __restrict__ slot_of) {
   for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n_edges;
        i += uint64_t(gridDim.x) * blockDim.x) {
     if (size[i] < 2) continue;
-    unsigned long long pos = hash[i] & mask;
+    const unsigned long long h = hash[i];
+    const unsigned long long tag = h >> 32;
+    const unsigned long long mine = (tag << 32) | i;
+    unsigned long long pos = h & mask;
     while (true) {
-      uint32_t cur = slots[pos];
-      if (cur == kEmpty32) {
-        uint32_t prev = atomicCAS(&slots[pos], kEmpty32, uint32_t(i));
-        if (prev == kEmpty32) break;
+      unsigned long long cur = slots[pos];
+      if (cur == kEmpty64) {
+        const unsigned long long prev = atomicCAS(&slots[pos], kEmpty64, mine);
+        if (prev == kEmpty64) break;
         cur = prev;
       }
-      if (same_tuple(sm, off, size, hash, cur, i)) {
-        atomicMin(&slots[pos], uint32_t(i));
+      if ((cur >> 32) == tag && same_tuple(sm, off, size, hash, uint32_t(cur), i)) {
+        atomicMin(&slots[pos], mine);
         break;
       }
       pos = (pos + 1) & mask;
     }
+    slot_of[i] = pos;
   }
 }
 
@@ -137,18 +146,6 @@ __global__ void k_dedup_insert(const uint32_t* __restrict__ sm, const uint64_t* 
 constexpr uint32_t kTile = 256;
 constexpr int kTileN = 5;   // unique, unique of size 2, 3, 4, members of the unique
 
-__device__ inline bool first_occurrence(const uint32_t* sm, const uint64_t* off, const uint32_t* size,
-                                        const unsigned long long* hash, uint64_t i, const uint32_t* slots,
-                                        unsigned long long mask) {
-  unsigned long long pos = hash[i] & mask;
-  while (true) {
-    const uint32_t cur = slots[pos];
-    if (cur == kEmpty32) return false;   // cannot happen: i was inserted
-    if (same_tuple(sm, off, size, hash, cur, i)) return cur == uint32_t(i);
-    pos = (pos + 1) & mask;
-  }
-}
-
 // Per-thread contribution of hyperedge i to the five tile counters.
 __device__ inline void tile_terms(uint32_t first, uint32_t s, uint32_t t[kTileN]) {
   t[0] = first;
@@ -158,21 +155,19 @@ __device__ inline void tile_terms(uint32_t first, uint32_t s, uint32_t t[kTileN]
   t[4] = first ? s : 0;
 }
 
-__global__ void __launch_bounds__(kTile) k_first_tiles(const uint32_t* __restrict__ sm,
-                                                        const uint64_t* __restrict__ off,
-                                                        const uint32_t* __restrict__ size,
-                                                        const unsigned long long* __restrict__ hash, uint64_t n_edges,
-                                                        const uint32_t* __restrict__ slots, unsigned long long mask,
+__global__ void __launch_bounds__(kTile) k_first_tiles(const uint32_t* __restrict__ size, uint64_t n_edges,
+                                                        const unsigned long long* __restrict__ slots,
+                                                        const unsigned long long* __restrict__ slot_of,
                                                         uint8_t* __restrict__ first_out,
-                                                        unsigned long long* __restrict__ tile_cnt, DevFlags* flags) {
-  __shared__ unsigned long long part[kTileN][kTile / kWave];
+                                                        uint32_t* __restrict__ tile_cnt, DevFlags* flags) {
+  __shared__ uint32_t part[kTileN][kTile / kWave];
   const uint64_t i = uint64_t(blockIdx.x) * kTile + threadIdx.x;
   uint32_t first = 0, s = 0;
   unsigned long long singles = 0, dups = 0;
   if (i < n_edges) {
     s = size[i];
     if (s >= 2) {
-      first = first_occurrence(sm, off, size, hash, i, slots, mask);
+      first = uint32_t(slots[slot_of[i]]) == uint32_t(i);
       dups = !first;
     } else if (s == 1) {
       singles = 1;
@@ -183,7 +178,8 @@ __global__ void __launch_bounds__(kTile) k_first_tiles(const uint32_t* __restric
   tile_terms(first, s, t);
   const int wv = threadIdx.x / kWave;
   for (int k = 0; k < kTileN; ++k) {
-    const unsigned long long w = wave_sum((unsigned long long)t[k]);
+    uint32_t w;
+    (void)wave_exclusive_scan(t[k], &w);
     if ((threadIdx.x & (kWave - 1)) == 0) part[k][wv] = w;
   }
   singles = wave_sum(singles);
@@ -194,42 +190,50 @@ __global__ void __launch_bounds__(kTile) k_first_tiles(const uint32_t* __restric
   }
   __syncthreads();
   if (threadIdx.x < kTileN) {
-    unsigned long long sum = 0;
+    uint32_t sum = 0;
     for (int q = 0; q < int(kTile / kWave); ++q) sum += part[threadIdx.x][q];
     tile_cnt[uint64_t(blockIdx.x) * kTileN + threadIdx.x] = sum;
   }
 }
 
-// Exclusive scan of the tile counters in place (one workgroup of 1024), and
-// the five totals.
-__global__ void __launch_bounds__(1024) k_tile_scan(unsigned long long* __restrict__ tile_cnt, uint64_t n_tiles,
+// Exclusive scan of the tile counters in place, and the five totals.  One
+// workgroup of 1024: thread t takes a run of consecutive tiles, the runs'
+// sums are scanned across the workgroup, and each thread then writes the
+// offsets of its run.  Every count is below 2^32 (so are the incidences).
+__global__ void __launch_bounds__(1024) k_tile_scan(uint32_t* __restrict__ tile_cnt, uint64_t n_tiles,
                                                     unsigned long long* __restrict__ totals) {
-  __shared__ unsigned long long wsum[1024 / kWave];
-  __shared__ unsigned long long carry;
+  __shared__ uint32_t wsum[kTileN][1024 / kWave];
   const uint32_t lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+  const uint64_t per = (n_tiles + 1023) / 1024;
+  const uint64_t t0 = min(n_tiles, uint64_t(threadIdx.x) * per), t1 = min(n_tiles, t0 + per);
+  uint32_t pre[kTileN];
+#pragma unroll
+  for (int k = 0; k < kTileN; ++k) pre[k] = 0;
+  for (uint64_t t = t0; t < t1; ++t) {
+#pragma unroll
+    for (int k = 0; k < kTileN; ++k) pre[k] += tile_cnt[t * kTileN + k];
+  }
+#pragma unroll
   for (int k = 0; k < kTileN; ++k) {
-    if (threadIdx.x == 0) carry = 0;
-    __syncthreads();
-    for (uint64_t c0 = 0; c0 < n_tiles; c0 += 1024) {
-      const uint64_t t = c0 + threadIdx.x;
-      const unsigned long long x = t < n_tiles ? tile_cnt[t * kTileN + k] : 0;
-      // inclusive wave scan
-      unsigned long long y = x;
-      for (int d = 1; d < kWave; d <<= 1) {
-        const uint32_t lo = __shfl_up(uint32_t(y), d, kWave), hi = __shfl_up(uint32_t(y >> 32), d, kWave);
-        if (int(lane) >= d) y += (unsigned long long)hi << 32 | lo;
-      }
-      if (lane == kWave - 1) wsum[wv] = y;
-      __syncthreads();
-      unsigned long long before = carry;
-      for (uint32_t q = 0; q < wv; ++q) before += wsum[q];
-      if (t < n_tiles) tile_cnt[t * kTileN + k] = before + y - x;
-      __syncthreads();
-      if (threadIdx.x == 1023) carry = before + y;
-      __syncthreads();
+    uint32_t tot;
+    pre[k] = wave_exclusive_scan(pre[k], &tot);
+    if (lane == 0) wsum[k][wv] = tot;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < kTileN; ++k)
+    for (uint32_t q = 0; q < wv; ++q) pre[k] += wsum[k][q];
+  for (uint64_t t = t0; t < t1; ++t) {
+#pragma unroll
+    for (int k = 0; k < kTileN; ++k) {
+      const uint32_t x = tile_cnt[t * kTileN + k];
+      tile_cnt[t * kTileN + k] = pre[k];
+      pre[k] += x;
     }
-    if (threadIdx.x == 0) totals[k] = carry;
-    __syncthreads();
+  }
+  if (threadIdx.x == 1023) {
+#pragma unroll
+    for (int k = 0; k < kTileN; ++k) totals[k] = pre[k];
   }
 }
 
@@ -245,7 +249,11 @@ struct GatherOut {
   Set128 hs3, hs4;
   uint32_t* bits;
   uint32_t W;
+  // degree counters, R (a power of two) per node, node-major: a hyperedge at
+  // position p of its stratum counts in copy p & (R - 1) of each member, so
+  // that no counter takes more than about 1/R of its node's incidences
   uint32_t *deg2, *deg3, *deg4;
+  uint32_t R;
   unsigned long long n_unique, n_members;
 };
 
@@ -253,7 +261,7 @@ __global__ void __launch_bounds__(kTile) k_gather_tiles(const uint32_t* __restri
                                                          const uint64_t* __restrict__ off,
                                                          const uint32_t* __restrict__ size, uint64_t n_edges,
                                                          const uint8_t* __restrict__ first_in,
-                                                         const unsigned long long* __restrict__ tile_off,
+                                                         const uint32_t* __restrict__ tile_off,
                                                          GatherOut g) {
   __shared__ uint32_t part[kTileN][kTile / kWave];
   const uint64_t i = uint64_t(blockIdx.x) * kTile + threadIdx.x;
@@ -294,8 +302,9 @@ __global__ void __launch_bounds__(kTile) k_gather_tiles(const uint32_t* __restri
       atomicOr(&g.bits[uint64_t(a) * g.W + (b >> 5)], 1u << (b & 31));
       atomicOr(&g.bits[uint64_t(b) * g.W + (a >> 5)], 1u << (a & 31));
     }
-    atomicAdd(&g.deg2[a], 1u);
-    atomicAdd(&g.deg2[b], 1u);
+    const uint32_t cp = uint32_t(pos[1]) & (g.R - 1);
+    atomicAdd(&g.deg2[uint64_t(a) * g.R + cp], 1u);
+    atomicAdd(&g.deg2[uint64_t(b) * g.R + cp], 1u);
   } else if (s == 3 || s == 4) {
     uint32_t* e = s == 3 ? g.e3 + 3 * pos[2] : g.e4 + 4 * pos[3];
     for (uint32_t j = 0; j < s; ++j) e[j] = m[j];
@@ -305,11 +314,12 @@ __global__ void __launch_bounds__(kTile) k_gather_tiles(const uint32_t* __restri
     while (atomicCAS(set.slot + 2 * h, kEmpty64, key.hi) != kEmpty64) h = (h + 1) & set.mask;
     set.slot[2 * h + 1] = key.lo;
     uint32_t* deg = s == 3 ? g.deg3 : g.deg4;
-    for (uint32_t j = 0; j < s; ++j) atomicAdd(&deg[m[j]], 1u);
+    const uint32_t cp = uint32_t(s == 3 ? pos[2] : pos[3]) & (g.R - 1);
+    for (uint32_t j = 0; j < s; ++j) atomicAdd(&deg[uint64_t(m[j]) * g.R + cp], 1u);
   }
 }
 
-// Up to eight fills in one launch.
+// Up to ten fills in one launch.
 struct FillRegions {
   void* ptr[10];
   unsigned long long count[10];
@@ -328,39 +338,54 @@ __global__ void k_multi_fill(FillRegions r) {
   }
 }
 
-// Exclusive scans of the three degree arrays into row offsets (n + 1
-// entries each) and, for the incidence lists, fill cursors.  One workgroup
-// of 1024 per array.
+// Exclusive scans of the three degree arrays (n nodes x R copies) into row
+// offsets o[v] = (scan at v * R), n + 1 entries, and, for the incidence lists,
+// fill cursors c of every (node, copy).  One workgroup of 1024 per array.
 __global__ void __launch_bounds__(1024) k_scan_degrees(const uint32_t* __restrict__ d0, uint32_t* __restrict__ o0,
                                                        const uint32_t* __restrict__ d1, uint32_t* __restrict__ o1,
                                                        uint32_t* __restrict__ c1, const uint32_t* __restrict__ d2,
-                                                       uint32_t* __restrict__ o2, uint32_t* __restrict__ c2, uint32_t n) {
+                                                       uint32_t* __restrict__ o2, uint32_t* __restrict__ c2, uint32_t n,
+                                                       uint32_t R) {
   __shared__ uint32_t wsum[1024 / kWave];
   __shared__ uint32_t carry;
   const uint32_t* d = blockIdx.x == 0 ? d0 : blockIdx.x == 1 ? d1 : d2;
   uint32_t* o = blockIdx.x == 0 ? o0 : blockIdx.x == 1 ? o1 : o2;
   uint32_t* c = blockIdx.x == 0 ? nullptr : blockIdx.x == 1 ? c1 : c2;
   const uint32_t lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+  const uint32_t m = n * R;
   if (threadIdx.x == 0) carry = 0;
   __syncthreads();
-  for (uint32_t c0 = 0; c0 < n; c0 += 1024) {
+  for (uint32_t c0 = 0; c0 < m; c0 += 1024) {
     const uint32_t t = c0 + threadIdx.x;
-    const uint32_t x = t < n ? d[t] : 0;
+    const uint32_t x = t < m ? d[t] : 0;
     uint32_t tot;
     const uint32_t ex = wave_exclusive_scan(x, &tot);
     if (lane == 0) wsum[wv] = tot;
     __syncthreads();
     uint32_t before = carry;
     for (uint32_t q = 0; q < wv; ++q) before += wsum[q];
-    if (t < n) {
-      o[t] = before + ex;
+    if (t < m) {
       if (c) c[t] = before + ex;
+      if ((t & (R - 1)) == 0) o[t / R] = before + ex;
     }
     __syncthreads();
     if (threadIdx.x == 1023) carry = before + ex + x;
     __syncthreads();
   }
   if (threadIdx.x == 0) o[n] = carry;
+}
+
+// Row offsets o[v] = s[v * R] for v = 0..n from scans s of n * R + 1 entries
+// (the last one the total), for three arrays.
+__global__ void k_offsets_of_copies(const uint32_t* __restrict__ s0, uint32_t* __restrict__ o0,
+                                    const uint32_t* __restrict__ s1, uint32_t* __restrict__ o1,
+                                    const uint32_t* __restrict__ s2, uint32_t* __restrict__ o2, uint32_t n,
+                                    uint32_t R) {
+  for (uint64_t v = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; v <= n; v += uint64_t(gridDim.x) * blockDim.x) {
+    o0[v] = s0[v * R];
+    o1[v] = s1[v * R];
+    o2[v] = s2[v * R];
+  }
 }
 
 // Sorted pairwise rows read off the adjacency bit rows: one wavefront per
@@ -386,16 +411,20 @@ __global__ void k_rows_from_bits(const uint32_t* __restrict__ bits, uint32_t n, 
   }
 }
 
-// Incidence lists of the 3- and 4-node hyperedges (positions in any order).
+// Incidence lists of the 3- and 4-node hyperedges (positions in any order):
+// hyperedge i fills through the cursor of copy i & (R - 1) of each member,
+// the copy its degree was counted in.
 __global__ void k_inc_fill(const uint32_t* __restrict__ e3, uint64_t n3, uint32_t* cur3, uint32_t* idx3,
-                           const uint32_t* __restrict__ e4, uint64_t n4, uint32_t* cur4, uint32_t* idx4) {
+                           const uint32_t* __restrict__ e4, uint64_t n4, uint32_t* cur4, uint32_t* idx4, uint32_t R) {
   for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n3 + n4;
        i += uint64_t(gridDim.x) * blockDim.x) {
     if (i < n3) {
-      for (int j = 0; j < 3; ++j) idx3[atomicAdd(&cur3[e3[3 * i + j]], 1u)] = uint32_t(i);
+      const uint32_t cp = uint32_t(i) & (R - 1);
+      for (int j = 0; j < 3; ++j) idx3[atomicAdd(&cur3[uint64_t(e3[3 * i + j]) * R + cp], 1u)] = uint32_t(i);
     } else {
       const uint64_t q = i - n3;
-      for (int j = 0; j < 4; ++j) idx4[atomicAdd(&cur4[e4[4 * q + j]], 1u)] = uint32_t(q);
+      const uint32_t cp = uint32_t(q) & (R - 1);
+      for (int j = 0; j < 4; ++j) idx4[atomicAdd(&cur4[uint64_t(e4[4 * q + j]) * R + cp], 1u)] = uint32_t(q);
     }
   }
 }
@@ -455,62 +484,87 @@ int node_bits(uint32_t n_nodes) {
   return b;
 }
 
-int build(hm_graph* H, const uint32_t* members_in, const uint64_t* offsets_in, uint64_t n_edges, int mem_kind,
-          hipStream_t st) {
-  Temps tmp(st);
-  uint64_t nnz = 0;
-  const uint32_t* members = members_in;
-  const uint64_t* offsets = offsets_in;
-  if (mem_kind == HM_MEM_HOST) {
-    nnz = offsets_in[n_edges];
-    uint32_t* dm = nullptr;
-    uint64_t* doff = nullptr;
-    HM_TRY(tmp.get(&dm, nnz));
-    HM_TRY(tmp.get(&doff, n_edges + 1));
-    if (nnz) HM_HIP(hipMemcpyAsync(dm, members_in, nnz * sizeof(uint32_t), hipMemcpyHostToDevice, st));
-    HM_HIP(hipMemcpyAsync(doff, offsets_in, (n_edges + 1) * sizeof(uint64_t), hipMemcpyHostToDevice, st));
-    members = dm;
-    offsets = doff;
-  } else {
-    uint64_t first = 0;
-    HM_HIP(hipMemcpyAsync(&first, offsets_in, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
-    HM_HIP(hipMemcpyAsync(&nnz, offsets_in + n_edges, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
-    HM_HIP(hipStreamSynchronize(st));
-    if (first != 0) {
-      set_error("offsets[0] must be 0");
-      return HM_EINVAL;
+// Copies of each node's degree counters (see GatherOut): a power of two up to
+// 16, with at most 2^22 counters per array.
+uint32_t degree_copies(uint64_t n_nodes) {
+  uint32_t R = 1;
+  while (R < 16 && n_nodes * R * 2 <= (1ull << 22)) R *= 2;
+  return R;
+}
+
+// What the build reads back once: validation flags and the five totals.  It
+// lands in pinned host memory, taken from a pool kept for the process.
+struct Report {
+  DevFlags flags;
+  unsigned long long totals[kTileN];
+};
+static_assert(sizeof(Report) % 8 == 0, "report is cleared as 64-bit words");
+
+std::mutex g_report_mu;
+std::vector<Report*> g_report_pool;
+
+struct PinnedReport {
+  Report* p = nullptr;
+  int take() {
+    {
+      std::lock_guard<std::mutex> lock(g_report_mu);
+      if (!g_report_pool.empty()) {
+        p = g_report_pool.back();
+        g_report_pool.pop_back();
+        return HM_OK;
+      }
     }
+    void* q = nullptr;
+    if (hipHostMalloc(&q, sizeof(Report), hipHostMallocDefault) != hipSuccess) {
+      (void)hipGetLastError();
+      set_error("pinned host allocation failed");
+      return HM_ENOMEM;
+    }
+    p = static_cast<Report*>(q);
+    return HM_OK;
   }
-  if (mem_kind == HM_MEM_HOST && offsets_in[0] != 0) {
-    set_error("offsets[0] must be 0");
-    return HM_EINVAL;
+  ~PinnedReport() {
+    if (!p) return;
+    std::lock_guard<std::mutex> lock(g_report_mu);
+    g_report_pool.push_back(p);
   }
-  if (nnz > 0xFFFFFFFFull) {
+};
+
+int build(hm_graph* H, const uint32_t* members_in, const uint64_t* offsets_in, uint64_t n_edges, uint64_t n_members,
+          int mem_kind, hipStream_t st) {
+  Temps tmp(st);
+  if (n_members > 0xFFFFFFFFull) {
     set_error("more than 2^32-1 incidences are not supported");
     return HM_EUNSUPPORTED;
   }
+  const uint32_t* members = members_in;
+  const uint64_t* offsets = offsets_in;
+  if (mem_kind == HM_MEM_HOST) {
+    uint32_t* dm = nullptr;
+    uint64_t* doff = nullptr;
+    HM_TRY(tmp.get(&dm, n_members));
+    HM_TRY(tmp.get(&doff, n_edges + 1));
+    if (n_members) HM_HIP(hipMemcpyAsync(dm, members_in, n_members * sizeof(uint32_t), hipMemcpyHostToDevice, st));
+    HM_HIP(hipMemcpyAsync(doff, offsets_in, (n_edges + 1) * sizeof(uint64_t), hipMemcpyHostToDevice, st));
+    members = dm;
+    offsets = doff;
+  }
   const uint64_t E = n_edges;
   const uint64_t n_tiles = (E + kTile - 1) / kTile;
-  // validation flags and the five totals share one block, read back at once
-  struct Report {
-    DevFlags flags;
-    unsigned long long totals[kTileN];
-  };
-  static_assert(sizeof(Report) % 8 == 0, "report is cleared as 64-bit words");
   Report* report = nullptr;
-  uint32_t *sm = nullptr, *size = nullptr, *slots = nullptr;
-  unsigned long long *hash = nullptr, *tile_cnt = nullptr;
+  uint32_t *sm = nullptr, *size = nullptr, *tile_cnt = nullptr;
+  unsigned long long *hash = nullptr, *slots = nullptr, *slot_of = nullptr;
   uint8_t* first = nullptr;
   const unsigned long long cap = pow2_capacity(E);
   HM_TRY(tmp.get(&report, 1));
-  HM_TRY(tmp.get(&sm, nnz));
+  HM_TRY(tmp.get(&sm, n_members));
   HM_TRY(tmp.get(&size, E));
   HM_TRY(tmp.get(&hash, E));
   HM_TRY(tmp.get(&slots, cap));
+  HM_TRY(tmp.get(&slot_of, E));
   HM_TRY(tmp.get(&first, E));
   HM_TRY(tmp.get(&tile_cnt, n_tiles * kTileN));
   DevFlags* flags = &report->flags;
-  unsigned long long* totals = report->totals;
   {
     FillRegions r{};
     r.ptr[0] = report;
@@ -523,27 +577,28 @@ int build(hm_graph* H, const uint32_t* members_in, const uint64_t* offsets_in, u
     r.wide[1] = 0;
     r.ptr[2] = slots;
     r.count[2] = cap;
-    r.value[2] = kEmpty32;
-    r.wide[2] = 0;
+    r.value[2] = kEmpty64;
+    r.wide[2] = 1;
     r.n = 3;
     k_multi_fill<<<grid_for(cap), 256, 0, st>>>(r);
   }
   if (E) {
     // validate and sort; collapse repeated hyperedges onto first occurrences
-    k_prepare<<<grid_for(E), 256, 0, st>>>(members, offsets, E, nnz, H->n_nodes, sm, size, hash, flags);
-    k_dedup_insert<<<grid_for(E), 256, 0, st>>>(sm, offsets, size, hash, E, slots, cap - 1);
-    k_first_tiles<<<unsigned(n_tiles), kTile, 0, st>>>(sm, offsets, size, hash, E, slots, cap - 1, first, tile_cnt,
-                                                       flags);
-    k_tile_scan<<<1, 1024, 0, st>>>(tile_cnt, n_tiles, totals);
+    k_prepare<<<grid_for(E), 256, 0, st>>>(members, offsets, E, n_members, H->n_nodes, sm, size, hash, flags);
+    k_dedup_insert<<<grid_for(E), 256, 0, st>>>(sm, offsets, size, hash, E, slots, cap - 1, slot_of);
+    k_first_tiles<<<unsigned(n_tiles), kTile, 0, st>>>(size, E, slots, slot_of, first, tile_cnt, flags);
+    k_tile_scan<<<1, 1024, 0, st>>>(tile_cnt, n_tiles, report->totals);
     HM_HIP(hipGetLastError());
   }
-  Report rep;
-  HM_HIP(hipMemcpyAsync(&rep, report, sizeof(rep), hipMemcpyDeviceToHost, st));
+  PinnedReport rep;
+  HM_TRY(rep.take());
+  HM_HIP(hipMemcpyAsync(rep.p, report, sizeof(Report), hipMemcpyDeviceToHost, st));
   HM_HIP(hipStreamSynchronize(st));
-  const DevFlags& got = rep.flags;
-  const unsigned long long* tot = rep.totals;
+  const DevFlags got = rep.p->flags;
+  unsigned long long tot[kTileN];
+  for (int k = 0; k < kTileN; ++k) tot[k] = rep.p->totals[k];
   if (got.err) {
-    const char* what = (got.err & kErrOffsets) ? "offsets decrease or exceed offsets[n_edges]"
+    const char* what = (got.err & kErrOffsets) ? "offsets[0] is not 0, or offsets decrease or exceed n_members"
                        : (got.err & kErrEmpty) ? "an empty hyperedge"
                        : (got.err & kErrBadId) ? "a node id >= n_nodes"
                                                : "a node repeated inside a hyperedge";
@@ -560,6 +615,8 @@ int build(hm_graph* H, const uint32_t* members_in, const uint64_t* offsets_in, u
   H->n_unique_members = tot[4];
   const uint64_t n2 = H->n_by_size[2], n3 = H->n_by_size[3], n4 = H->n_by_size[4];
   const uint64_t N = H->n_nodes;
+  const uint32_t R = degree_copies(N);
+  const uint64_t NR = N * R;
 
   // everything the unique hyperedges are written into
   HM_TRY(owned(&H->e2, 2 * n2));
@@ -580,11 +637,11 @@ int build(hm_graph* H, const uint32_t* members_in, const uint64_t* offsets_in, u
     HM_TRY(owned(&H->bits, N * H->words));
   }
   uint32_t *deg2 = nullptr, *deg3 = nullptr, *deg4 = nullptr, *cur3 = nullptr, *cur4 = nullptr;
-  HM_TRY(tmp.get(&deg2, N));
-  HM_TRY(tmp.get(&deg3, N));
-  HM_TRY(tmp.get(&deg4, N));
-  HM_TRY(tmp.get(&cur3, N));
-  HM_TRY(tmp.get(&cur4, N));
+  HM_TRY(tmp.get(&deg2, NR));
+  HM_TRY(tmp.get(&deg3, NR));
+  HM_TRY(tmp.get(&deg4, NR));
+  HM_TRY(tmp.get(&cur3, NR + 1));
+  HM_TRY(tmp.get(&cur4, NR + 1));
   HM_TRY(owned(&H->g2_off, N + 1));
   HM_TRY(owned(&H->g2_adj, 2 * n2));
   HM_TRY(owned(&H->i3_off, N + 1));
@@ -607,10 +664,11 @@ int build(hm_graph* H, const uint32_t* members_in, const uint64_t* offsets_in, u
     add(H->hs4.slot, 2 * c4, kEmpty64, 1);
     add(H->sample_hist, 256 + 8, 0, 1);
     add(H->hist, 4 * 256, 0, 1);
-    add(deg2, N, 0, 0);
-    add(deg3, N, 0, 0);
-    add(deg4, N, 0, 0);
+    add(deg2, NR, 0, 0);
+    add(deg3, NR, 0, 0);
+    add(deg4, NR, 0, 0);
     if (keep_bits) add(H->bits, N * H->words, 0, 0);
+    if (H->n_unique == 0) add(H->all_off, 1, 0, 1);
     unsigned long long most = 0;
     for (uint32_t k = 0; k < r.n; ++k) most = std::max(most, r.count[k]);
     k_multi_fill<<<grid_for(most), 256, 0, st>>>(r);
@@ -630,26 +688,30 @@ int build(hm_graph* H, const uint32_t* members_in, const uint64_t* offsets_in, u
     g.deg2 = deg2;
     g.deg3 = deg3;
     g.deg4 = deg4;
+    g.R = R;
     g.n_unique = H->n_unique;
     g.n_members = H->n_unique_members;
     k_gather_tiles<<<unsigned(n_tiles), kTile, 0, st>>>(sm, offsets, size, E, first, tile_cnt, g);
   }
-  if (H->n_unique == 0) HM_TRY(fill_u64(H->all_off, 0, 1, st));
   HM_HIP(hipGetLastError());
 
-  // row offsets: pairwise rows, incidence lists of 3- and 4-node hyperedges
-  if (N <= 64 * 1024) {
-    k_scan_degrees<<<3, 1024, 0, st>>>(deg2, H->g2_off, deg3, H->i3_off, cur3, deg4, H->i4_off, cur4, uint32_t(N));
+  // row offsets: pairwise rows, incidence lists of 3- and 4-node hyperedges;
+  // fill cursors per (node, copy)
+  if (NR <= 64 * 1024) {
+    k_scan_degrees<<<3, 1024, 0, st>>>(deg2, H->g2_off, deg3, H->i3_off, cur3, deg4, H->i4_off, cur4, uint32_t(N), R);
     HM_HIP(hipGetLastError());
   } else {
-    HM_TRY(scan_exclusive_u32(deg2, H->g2_off, N, H->g2_off + N, st));
-    HM_TRY(scan_exclusive_u32(deg3, H->i3_off, N, H->i3_off + N, st));
-    HM_TRY(scan_exclusive_u32(deg4, H->i4_off, N, H->i4_off + N, st));
-    HM_TRY(copy_u32(H->i3_off, cur3, N, st));
-    HM_TRY(copy_u32(H->i4_off, cur4, N, st));
+    uint32_t* cur2 = nullptr;
+    HM_TRY(tmp.get(&cur2, NR + 1));
+    HM_TRY(scan_exclusive_u32(deg2, cur2, NR, cur2 + NR, st));
+    HM_TRY(scan_exclusive_u32(deg3, cur3, NR, cur3 + NR, st));
+    HM_TRY(scan_exclusive_u32(deg4, cur4, NR, cur4 + NR, st));
+    k_offsets_of_copies<<<grid_for(N + 1), 256, 0, st>>>(cur2, H->g2_off, cur3, H->i3_off, cur4, H->i4_off,
+                                                         uint32_t(N), R);
+    HM_HIP(hipGetLastError());
   }
   if (n3 + n4) {
-    k_inc_fill<<<grid_for(n3 + n4), 256, 0, st>>>(H->e3, n3, cur3, H->i3_idx, H->e4, n4, cur4, H->i4_idx);
+    k_inc_fill<<<grid_for(n3 + n4), 256, 0, st>>>(H->e3, n3, cur3, H->i3_idx, H->e4, n4, cur4, H->i4_idx, R);
     HM_HIP(hipGetLastError());
   }
   if (n2) {
@@ -680,31 +742,20 @@ int build(hm_graph* H, const uint32_t* members_in, const uint64_t* offsets_in, u
   return HM_OK;
 }
 
-void release(hm_graph* H) {
-  dfree(H->e2);
-  dfree(H->e3);
-  dfree(H->e4);
-  dfree(H->all_members);
-  dfree(H->all_off);
-  dfree(H->hs2.slot);
-  dfree(H->hs3.slot);
-  dfree(H->hs4.slot);
-  dfree(H->g2_off);
-  dfree(H->g2_adj);
-  dfree(H->g2_eid);
-  dfree(H->i3_off);
-  dfree(H->i3_idx);
-  dfree(H->i4_off);
-  dfree(H->i4_idx);
-  dfree(H->bits);
-  dfree(H->hist);
-  dfree(H->sample_hist);
-  dfree(H->pl_keys);
-  dfree(H->pl_edge);
-  dfree(H->ns_tri);
-  dfree(H->ns_nbr);
-  dfree(H->ns_h3);
-  dfree(H->es);
+// Device memory of a graph.  With a stream, it returns to the cache once the
+// work enqueued on that stream so far has run; without, at once (its users
+// have been synchronised).
+void release(hm_graph* H, hipStream_t st = nullptr, bool ordered = false) {
+  void* ps[] = {H->e2,     H->e3,      H->e4,     H->all_members, H->all_off, H->hs2.slot, H->hs3.slot,
+                H->hs4.slot, H->g2_off, H->g2_adj, H->g2_eid,      H->i3_off,  H->i3_idx,   H->i4_off,
+                H->i4_idx, H->bits,     H->hist,   H->sample_hist, H->pl_keys, H->pl_edge,  H->ns_tri,
+                H->ns_nbr, H->ns_h3,    H->es};
+  constexpr size_t n = sizeof(ps) / sizeof(ps[0]);
+  if (ordered) {
+    dfree_on(ps, n, st);
+  } else {
+    for (size_t i = 0; i < n; ++i) dfree(ps[i]);
+  }
   if (H->null_plan) destroy_null_plan(H->null_plan);
   H->null_plan = nullptr;
   if (H->proposal) destroy_proposal_cache(H->proposal);
@@ -716,14 +767,14 @@ void release(hm_graph* H) {
 
 extern "C" {
 
-int hm_graph_create(const uint32_t* members, const uint64_t* offsets, uint64_t n_edges, uint32_t n_nodes,
-                    int mem_kind, void* stream, hm_graph** out) {
+int hm_graph_create(const uint32_t* members, const uint64_t* offsets, uint64_t n_edges, uint64_t n_members,
+                    uint32_t n_nodes, int mem_kind, void* stream, hm_graph** out) {
   if (!out) {
     hm::set_error("out is NULL");
     return HM_EINVAL;
   }
   *out = nullptr;
-  if (!offsets || (!members && n_edges > 0)) {
+  if (!offsets || (!members && n_members > 0)) {
     hm::set_error("members/offsets must not be NULL");
     return HM_EINVAL;
   }
@@ -752,21 +803,29 @@ int hm_graph_create(const uint32_t* members, const uint64_t* offsets, uint64_t n
   }
   H->n_nodes = n_nodes;
   H->n_input = n_edges;
-  int rc = hm::build(H, members, offsets, n_edges, mem_kind, st);
+  int rc = hm::build(H, members, offsets, n_edges, n_members, mem_kind, st);
   if (rc != HM_OK) {
     (void)hipStreamSynchronize(st);
     hm::release(H);
     delete H;
     return rc;
   }
+  hm::note_use(H, st);
   *out = H;
   return HM_OK;
 }
 
 int hm_graph_destroy(hm_graph* H) {
   if (!H) return HM_OK;
-  (void)hipDeviceSynchronize();
-  hm::release(H);
+  // a graph used on one stream only, with no captured pipeline or proposal
+  // cache, is released in that stream's order; otherwise after a device-wide
+  // synchronisation
+  if (H->streams.size() == 1 && !H->null_plan && !H->proposal) {
+    hm::release(H, H->streams[0], true);
+  } else {
+    (void)hipDeviceSynchronize();
+    hm::release(H);
+  }
   delete H;
   return HM_OK;
 }

@@ -10,6 +10,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <string>
+#include <vector>
 
 #include "../../include/homotif.h"
 
@@ -238,6 +239,9 @@ struct hm_graph {
   // between calls (hist_dirty: a call failed part-way and left it unknown)
   unsigned long long* hist = nullptr;      // 4 x 256 counters
   mutable bool hist_dirty = false;
+  // the streams work on the graph was enqueued on (hm_graph_destroy releases
+  // the memory in stream order when there is only one)
+  mutable std::vector<hipStream_t> streams;
   // pairs inside 3-node hyperedges, sorted ((x << 32) | y), with the position
   // of their hyperedge in e3; built on first use without bit rows
   unsigned long long* pl_keys = nullptr;
@@ -259,3 +263,13 @@ struct hm_graph {
   // learned-proposal probabilities of the last model used with this graph
   hm::ProposalCache* proposal = nullptr;
 };
+
+namespace hm {
+// Record that work on H is enqueued on st (every entry point that enqueues
+// work on a graph calls this).
+inline void note_use(const hm_graph* H, hipStream_t st) {
+  for (hipStream_t s : H->streams)
+    if (s == st) return;
+  H->streams.push_back(st);
+}
+}  // namespace hm

@@ -591,6 +591,7 @@ int strata_bounds(const hm_graph* H, int k, uint64_t b[5]) {
 
 // standardised features of every hyperedge of size 2..k (device, n x 16)
 int features(const hm_graph* H, int k, float* X, Bufs& tmp, hipStream_t st) {
+  note_use(H, st);
   uint64_t b[5];
   const int ns = strata_bounds(H, k, b);
   const uint64_t n = b[ns];
@@ -615,6 +616,7 @@ int features(const hm_graph* H, int k, float* X, Bufs& tmp, hipStream_t st) {
 // Per-hyperedge contributions y (device, stratum rows), by enumerating each
 // hyperedge as a single sample (chunks of rows).
 int contributions(const hm_graph* H, int k, double* y, hipStream_t st) {
+  note_use(H, st);
   const ClassTables& t = class_tables();
   CountmaxArg cm;
   for (int c = 0; c < 256; ++c) cm.cm[c] = c < t.n_classes[k] ? t.countmax[k][c] : 1;
@@ -649,6 +651,7 @@ int contributions(const hm_graph* H, int k, double* y, hipStream_t st) {
 // Hansen-Hurwitz estimate from explicit draws (device indices) and weights.
 int hh_from_draws(const hm_graph* H, int k, const uint32_t* const idx[5], const uint64_t S[5], const double* w,
                   float* est, int64_t* raw, hipStream_t st) {
+  note_use(H, st);
   Bufs tmp;
   uint64_t total = 0, row0[5] = {0, 0, 0, 0, 0};
   for (int j = 2; j <= k; ++j) {
@@ -724,6 +727,7 @@ struct ProposalCache {
 void destroy_proposal_cache(ProposalCache* c) { delete c; }
 
 int build_proposal(const hm_graph* Hc, const hm_model* M, int k, hipStream_t st) {
+  note_use(Hc, st);
   hm_graph* H = const_cast<hm_graph*>(Hc);
   if (H->proposal && H->proposal->model_id == M->id && H->proposal->k == k) return HM_OK;
   if (H->proposal) {

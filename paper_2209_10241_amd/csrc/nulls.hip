@@ -1051,6 +1051,7 @@ int autotune(const hm_graph* H, NullPlan& P, hipStream_t st) {
 
 // Generate copies [c0, c0 + R) into members (R x T, device), synchronously.
 int null_copies(const hm_graph* H, uint32_t c0, uint32_t R, uint64_t seed, uint32_t* members, hipStream_t st) {
+  note_use(H, st);
   if (H->n_unique_members == 0 || R == 0) return HM_OK;
   NullPlan P;
   P.R = R;
@@ -1093,6 +1094,7 @@ int null_copies(const hm_graph* H, uint32_t c0, uint32_t R, uint64_t seed, uint3
 
 int count_nulls_impl(hm_graph* H, int k, uint32_t R, uint64_t seed, int64_t* real, int64_t* nulls, float* z,
                      hipStream_t st) {
+  note_use(H, st);
   const int C = class_tables().n_classes[k];
   const uint8_t *lut4 = nullptr, *lut3 = nullptr;
   HM_TRY(device_luts(H->device, &lut4, &lut3));

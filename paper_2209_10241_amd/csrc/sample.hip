@@ -949,6 +949,7 @@ uint32_t blocks_for(uint64_t items, uint64_t per_block, uint32_t cap) {
 // est (and raw) receive the scaled (and raw) counts.
 int launch_sampled(const hm_graph* H, int k, const uint32_t* const idx[5], const uint64_t S[5], uint64_t seed,
                    unsigned long long* rows, const uint64_t row0[5], float* est, int64_t* raw, hipStream_t st) {
+  note_use(H, st);
   const uint8_t *lut4 = nullptr, *lut3 = nullptr;
   HM_TRY(device_luts(H->device, &lut4, &lut3));
   const bool bits = H->bits != nullptr;

@@ -402,6 +402,7 @@ __global__ void k_ns_h3(View v, uint64_t n3, uint32_t* __restrict__ h3) {
 // first use: triangles at each node, the sum of its neighbours' degrees, and
 // its 3-node hyperedges by pairwise pattern.
 int ensure_node_stats(hm_graph* H, hipStream_t st) {
+  note_use(H, st);
   if (H->ns_tri) return HM_OK;
   const View v = view_of(H);
   const uint64_t n2 = H->n_by_size[2], n3 = H->n_by_size[3], N = H->n_nodes;
@@ -445,6 +446,7 @@ int ensure_node_stats(hm_graph* H, hipStream_t st) {
 // Per-pair statistics of H for the pair sampler without bit rows (layout in
 // hm_graph::es), built on first use.
 int ensure_edge_stats(hm_graph* H, hipStream_t st) {
+  note_use(H, st);
   if (H->es) return HM_OK;
   const View v = view_of(H);
   const uint64_t n2 = H->n_by_size[2], N = H->n_nodes;
@@ -503,6 +505,7 @@ int ensure_edge_stats(hm_graph* H, hipStream_t st) {
 
 // The pair -> 3-node hyperedge index of H, built on first use.
 int ensure_pair_links(hm_graph* H, hipStream_t st) {
+  note_use(H, st);
   if (H->pl_keys || H->n_by_size[3] == 0) return HM_OK;
   const uint64_t n = 3 * H->n_by_size[3];
   void *k = nullptr, *e = nullptr, *kt = nullptr, *et = nullptr;
@@ -544,6 +547,7 @@ PairLinks pair_links_of(const hm_graph* H) {
 // Fills the main, sub and G2 regions of H->hist (zeroed by the caller) except
 // case (a), which the caller counts.
 int count_sparse(const hm_graph* H, int k, hipStream_t st) {
+  note_use(H, st);
   const uint8_t *lut4 = nullptr, *lut3 = nullptr;
   HM_TRY(device_luts(H->device, &lut4, &lut3));
   const View v = view_of(H);

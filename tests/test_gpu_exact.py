@@ -168,6 +168,55 @@ def test_empty_hyperedge_is_rejected(hm):
         hm.hm_graph_create(np.array([0, 1], np.uint32), np.array([0, 2, 2], np.uint64), 3)
 
 
+@pytest.mark.parametrize("where", ["host", "device"])
+@pytest.mark.parametrize("offsets", [[1, 3, 5], [0, 3, 2], [0, 2, 7]], ids=["start", "decrease", "beyond"])
+def test_bad_offsets_are_rejected(hm, where, offsets):
+    """Offsets must start at 0, not decrease and stay within the members."""
+    import torch
+    m = np.array([0, 1, 2, 3, 4], np.uint32)
+    o = np.array(offsets, np.uint64)
+    if where == "device":
+        m = torch.from_numpy(m.astype(np.int32)).cuda()
+        o = torch.from_numpy(o.astype(np.int64)).cuda()
+    with pytest.raises(hm.HMError) as e:
+        hm.hm_graph_create(m, o, 6)
+    assert e.value.code == -1
+
+
+def test_members_beyond_the_last_offset_are_ignored(hm):
+    """Trailing entries of members that no hyperedge reaches do not count."""
+    import torch
+    h = W.random_small(78, 30, 200, {2: 0.5, 3: 0.3, 4: 0.2})
+    tail = np.array([29, 29, 29], np.uint32)
+    for dev in (False, True):
+        m = np.concatenate([h.members.astype(np.uint32), tail])
+        o = h.offsets.astype(np.uint64)
+        if dev:
+            m = torch.from_numpy(m.astype(np.int32)).cuda()
+            o = torch.from_numpy(o.astype(np.int64)).cuda()
+        with hm.hm_graph_create(m, o, h.n_nodes) as g:
+            assert np.array_equal(hm.count_exact(g, 4).cpu().numpy(), core.count_exact(h, 4))
+
+
+def test_many_graphs_created_and_destroyed_in_stream_order(hm):
+    """Graphs destroyed without a device-wide wait: memory released in stream
+    order is not reused before the work that reads it has run."""
+    import torch
+    hs = [W.random_small(90 + i, 40, 300, {2: 0.5, 3: 0.3, 4: 0.2}) for i in range(6)]
+    want = [core.count_exact(h, 4) for h in hs]
+    outs = []
+    for _ in range(3):
+        for h in hs:
+            m = torch.from_numpy(h.members.astype(np.int32)).cuda()
+            o = torch.from_numpy(h.offsets.astype(np.int64)).cuda()
+            g = hm.hm_graph_create(m, o, h.n_nodes)
+            outs.append(hm.count_exact(g, 4))
+            g.close()
+    torch.cuda.synchronize()
+    for i, c in enumerate(outs):
+        assert np.array_equal(c.cpu().numpy(), want[i % len(hs)]), i
+
+
 def test_wide_bit_rows(hm):
     """More than 64 words per bit row (N > 2048): the word loop of the pairs-only kernel."""
     base = W.random_small(3000, 80, 900, {2: 0.6, 3: 0.3, 4: 0.1})
