@@ -34,8 +34,9 @@ __global__ void __launch_bounds__(kThreads) k_case_a4(View v, uint64_t n4, const
     count_class(lut, h_main, h_sub, p, kPairBits4);
   }
   __syncthreads();
-  flush(h_main, hist + kMain, 256);
-  flush(h_sub, hist + kSub, 256);
+  unsigned long long* hc = hist_copy(hist, kExactHistStride);
+  flush(h_main, hc + kMain, 256);
+  flush(h_sub, hc + kSub, 256);
 }
 
 // (a) at order 3: one thread per 3-node hyperedge.
@@ -50,8 +51,9 @@ __global__ void __launch_bounds__(kThreads) k_case_a3(View v, uint64_t n3, const
   for (uint64_t i = uint64_t(blockIdx.x) * kThreads + threadIdx.x; i < n3; i += uint64_t(gridDim.x) * kThreads)
     count_class(lut, h_main, h_sub, a3_pattern(v, v.e3[3 * i], v.e3[3 * i + 1], v.e3[3 * i + 2]), kPairBits3);
   __syncthreads();
-  flush(h_main, hist + kMain, 256);
-  flush(h_sub, hist + kSub, 256);
+  unsigned long long* hc = hist_copy(hist, kExactHistStride);
+  flush(h_main, hc + kMain, 256);
+  flush(h_sub, hc + kSub, 256);
 }
 
 // counts[c] = main[c] + (c pairs-only ? g2[c] - sub[c] : 0), as int64
@@ -59,19 +61,26 @@ struct ClassMask {
   unsigned long long w[4];
 };
 
-// (one workgroup of 256 threads; leaves hist zero)
+// (one workgroup of 256 threads; sums the kHistCopies copies of hist and
+// leaves them zero)
 __global__ void k_combine(unsigned long long* __restrict__ hist, int n_classes, ClassMask pairs_only,
                           int64_t* __restrict__ counts) {
   const int c = threadIdx.x;
-  const unsigned long long m = hist[kMain + c], s = hist[kSub + c], g = hist[kG2 + c];
+  unsigned long long m = 0, s = 0, g = 0;
+  for (uint32_t q = 0; q < kHistCopies; ++q) {
+    unsigned long long* h = hist + uint64_t(q) * kExactHistStride;
+    m += h[kMain + c];
+    s += h[kSub + c];
+    g += h[kG2 + c];
+    h[kMain + c] = 0;
+    h[kSub + c] = 0;
+    h[kG2 + c] = 0;
+  }
   if (c < n_classes) {
     unsigned long long v = m;
     if ((pairs_only.w[c >> 6] >> (c & 63)) & 1ull) v += g - s;
     counts[c] = int64_t(v);
   }
-  hist[kMain + c] = 0;
-  hist[kSub + c] = 0;
-  hist[kG2 + c] = 0;
 }
 
 // All generators of one order in a single launch (bit rows), sized to the
@@ -127,9 +136,10 @@ __global__ void __launch_bounds__(kThreads) k_exact4_bits(ExactArgs a) {
   }
   c4_flush(acc, lut, h_g2);
   __syncthreads();
-  flush(h_main, a.hist + kMain, 256);
-  flush(h_sub, a.hist + kSub, 256);
-  flush(h_g2, a.hist + kG2, 256);
+  unsigned long long* hc = hist_copy(a.hist, kExactHistStride);
+  flush(h_main, hc + kMain, 256);
+  flush(h_sub, hc + kSub, 256);
+  flush(h_g2, hc + kG2, 256);
 }
 
 // Order 3: thread items [0, n2 * W) are the (pair, word) tasks of case (c),
@@ -157,9 +167,10 @@ __global__ void __launch_bounds__(kThreads) k_exact3_bits(ExactArgs a) {
   }
   c3_flush(acc, lut, h_g2);
   __syncthreads();
-  flush(h_main, a.hist + kMain, 256);
-  flush(h_sub, a.hist + kSub, 256);
-  flush(h_g2, a.hist + kG2, 256);
+  unsigned long long* hc = hist_copy(a.hist, kExactHistStride);
+  flush(h_main, hc + kMain, 256);
+  flush(h_sub, hc + kSub, 256);
+  flush(h_g2, hc + kG2, 256);
 }
 
 // Counting kernels keep per-class counters in LDS and flush them once per
@@ -219,7 +230,7 @@ int count_exact_impl(const hm_graph* H, int k, int64_t* counts, hipStream_t st) 
   // H->hist is zero between calls; a call that fails part-way clears it on
   // the next call
   if (H->hist_dirty) {
-    HM_TRY(fill_u64(H->hist, 0, 4 * 256, st));
+    HM_TRY(fill_u64(H->hist, 0, uint64_t(kHistCopies) * kExactHistStride, st));
     H->hist_dirty = false;
   }
   struct DirtyOnError {

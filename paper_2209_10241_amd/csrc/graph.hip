@@ -648,8 +648,8 @@ int build(hm_graph* H, const uint32_t* members_in, const uint64_t* offsets_in, u
   HM_TRY(owned(&H->i3_idx, 3 * n3));
   HM_TRY(owned(&H->i4_off, N + 1));
   HM_TRY(owned(&H->i4_idx, 4 * n4));
-  HM_TRY(owned(&H->hist, 4 * 256));
-  HM_TRY(owned(&H->sample_hist, 256 + 8));
+  HM_TRY(owned(&H->hist, uint64_t(kHistCopies) * kExactHistStride));
+  HM_TRY(owned(&H->sample_hist, uint64_t(kHistCopies) * kSampleHistStride + 8));
   {
     FillRegions r{};
     auto add = [&r](void* p, unsigned long long n, unsigned long long v, uint32_t wide) {
@@ -662,8 +662,8 @@ int build(hm_graph* H, const uint32_t* members_in, const uint64_t* offsets_in, u
     add(H->hs2.slot, c2, kEmpty64, 1);
     add(H->hs3.slot, 2 * c3, kEmpty64, 1);
     add(H->hs4.slot, 2 * c4, kEmpty64, 1);
-    add(H->sample_hist, 256 + 8, 0, 1);
-    add(H->hist, 4 * 256, 0, 1);
+    add(H->sample_hist, uint64_t(kHistCopies) * kSampleHistStride + 8, 0, 1);
+    add(H->hist, uint64_t(kHistCopies) * kExactHistStride, 0, 1);
     add(deg2, NR, 0, 0);
     add(deg3, NR, 0, 0);
     add(deg4, NR, 0, 0);

@@ -58,6 +58,11 @@ __device__ inline uint32_t upper_bound(const uint32_t* adj, uint32_t p, uint32_t
   }
   return p;
 }
+__device__ inline uint32_t wave_sum_u32(uint32_t x) {
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) x += __shfl_xor(x, o, kWave);
+  return x;
+}
 __device__ inline unsigned long long wave_sum(unsigned long long v) {
   uint32_t lo = uint32_t(v), hi = uint32_t(v >> 32);
 #pragma unroll
@@ -90,6 +95,11 @@ __device__ inline uint32_t wave_exclusive_scan(uint32_t v, uint32_t* total) {
 
 __device__ inline void load_lut(uint8_t* lut, const uint8_t* g, int n) {
   for (int i = threadIdx.x; i < n; i += blockDim.x) lut[i] = g[i];
+}
+
+// This workgroup's copy of a histogram kept in kHistCopies copies.
+__device__ inline unsigned long long* hist_copy(unsigned long long* hist, uint32_t stride) {
+  return hist + uint64_t(blockIdx.x & (kHistCopies - 1)) * stride;
 }
 
 __device__ inline void flush(unsigned long long* lds, unsigned long long* out, int n) {

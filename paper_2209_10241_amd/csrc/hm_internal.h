@@ -17,6 +17,13 @@
 namespace hm {
 
 constexpr int kWave = 64;
+// Device histograms that many workgroups add to are kept in kHistCopies
+// copies: workgroup b adds to copy b mod kHistCopies, so that no counter takes
+// the atomics of more than a kHistCopies-th of the workgroups; the kernel
+// that reads them sums the copies.
+constexpr uint32_t kHistCopies = 16;
+constexpr uint32_t kExactHistStride = 1024;   // per copy: main, sub, G2 regions, 256 unused
+constexpr uint32_t kSampleHistStride = 256;
 constexpr uint32_t kEmpty32 = 0xFFFFFFFFu;
 constexpr unsigned long long kEmpty64 = ~0ull;
 // adjacency bit rows are kept when the node count is at most this (the
@@ -235,9 +242,10 @@ struct hm_graph {
   uint32_t words = 0;
 
   // histogram scratch, reused by the counting calls (serialised per graph):
-  // main, sub and G2 regions of 256 counters (the fourth 256 unused); zero
-  // between calls (hist_dirty: a call failed part-way and left it unknown)
-  unsigned long long* hist = nullptr;      // 4 x 256 counters
+  // kHistCopies copies of main, sub and G2 regions of 256 counters (and 256
+  // unused); zero between calls (hist_dirty: a call failed part-way and left
+  // it unknown)
+  unsigned long long* hist = nullptr;      // kHistCopies x kExactHistStride counters
   mutable bool hist_dirty = false;
   // the streams work on the graph was enqueued on (hm_graph_destroy releases
   // the memory in stream order when there is only one)
@@ -255,8 +263,9 @@ struct hm_graph {
   // triangles, 4-cliques and 4-cycles through it; over its common neighbours
   // x: sum of t_{ux}, sum of t_{wx}, sum of deg x
   unsigned long long* es = nullptr;
-  // raw counters (256) of the sampled counting calls, then ([257], [258])
-  // the tail and head of their work queue; zero between calls
+  // raw counters of the sampled counting calls (kHistCopies copies of 256),
+  // then the tail and head of their work queue (the two words after one
+  // unused); zero between calls
   unsigned long long* sample_hist = nullptr;
   // buffers and captured HIP graph of the batched null-model pipeline
   hm::NullPlan* null_plan = nullptr;

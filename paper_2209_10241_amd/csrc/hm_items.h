@@ -173,6 +173,19 @@ __device__ inline void c4_word(uint32_t Nr, uint32_t Nx, uint32_t Ny, uint32_t g
   }
 }
 
+// Number of set bits of the bit row R (W words) at positions <= x; every
+// lane of the wavefront calls this and receives the count.
+__device__ inline uint32_t bits_upto(const uint32_t* R, uint32_t W, uint32_t x) {
+  const uint32_t lane = threadIdx.x & (kWave - 1);
+  const uint32_t xw = x >> 5;
+  uint32_t c = 0;
+  for (uint32_t w = lane; w < W && w <= xw; w += kWave) {
+    const uint32_t m = w < xw ? ~0u : (0xFFFFFFFFu >> (31 - (x & 31)));
+    c += __popc(R[w] & m);
+  }
+  return wave_sum_u32(c);
+}
+
 __device__ inline void c4_flush(const C4Acc& a, const uint8_t* lut, unsigned long long* h_g2);
 
 // ys: 64 words of wavefront-private LDS.  Every lane of the wavefront calls
@@ -185,9 +198,11 @@ __device__ inline void c4_bits_item(const View& v, uint32_t r, uint32_t x, const
   const uint32_t* Rr = v.bits + uint64_t(r) * W;
   const uint32_t* Rx = v.bits + uint64_t(x) * W;
   const uint32_t re = v.g2_off[r + 1];
-  const uint32_t p = upper_bound(v.g2_adj, v.g2_off[r], re, x);
   const uint32_t xe = v.g2_off[x + 1];
-  const uint32_t q = upper_bound(v.g2_adj, v.g2_off[x], xe, r);
+  // first neighbour of r above x and of x above r: the row start plus the
+  // number of set bits up to x (up to r) in the bit row
+  const uint32_t p = v.g2_off[r] + bits_upto(Rr, W, x);
+  const uint32_t q = v.g2_off[x] + bits_upto(Rx, W, r);
   const unsigned long long below = (1ull << lane) - 1ull;
   // |A| = 3 and |A| = 2: y over the neighbours of r above x, 64 at a time
   for (uint32_t base = p; base < re; base += kWave) {

@@ -45,12 +45,6 @@ __device__ inline uint64_t pl_lower(const PairLinks& pl, unsigned long long key)
 
 __device__ inline uint32_t deg2_of(const View& v, uint32_t x) { return v.g2_off[x + 1] - v.g2_off[x]; }
 
-__device__ inline uint32_t wave_sum_u32(uint32_t x) {
-#pragma unroll
-  for (int o = kWave / 2; o > 0; o >>= 1) x += __shfl_xor(x, o, kWave);
-  return x;
-}
-
 // |N(s) n N(x)| and, with y given, |N(s) n N(x) n N(y)|, over s's row (wave)
 __device__ inline void row_probe(const View& v, uint32_t s, uint32_t x, uint32_t y, uint32_t& cx, uint32_t& cy,
                                  uint32_t& cxy) {

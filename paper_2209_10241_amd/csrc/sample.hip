@@ -806,7 +806,7 @@ struct SampledArgs {
   const uint8_t* lut;
   uint32_t blocks[5];            // workgroups of strata 2, 3, 4 (in this order in the grid)
   unsigned long long* rows[5];   // per-sample rows (256 counters) of each stratum, or null
-  unsigned long long* hist;      // 256 raw counters, zero on entry; left zero after scaling
+  unsigned long long* hist;      // raw counters (kHistCopies x 256), zero on entry; left zero after scaling
   float* est;                    // null: no scaling (row mode)
   int64_t* raw;
   int n_classes;
@@ -835,7 +835,11 @@ struct SampledLds<4, false> {
 // makes the atomics of every workgroup of the sampler visible to it.
 __global__ void __launch_bounds__(kThreads) k_finish_sampled(SampledArgs a, ScaleArgs sc) {
   const int c = threadIdx.x;
-  const unsigned long long r = a.hist[c];
+  unsigned long long r = 0;
+  for (uint32_t q = 0; q < kHistCopies; ++q) {
+    r += a.hist[uint64_t(q) * kSampleHistStride + c];
+    a.hist[uint64_t(q) * kSampleHistStride + c] = 0;
+  }
   if (a.est && c < a.n_classes) {
     const int j = sc.maxcard[c];
     double e = 0.0;
@@ -843,7 +847,6 @@ __global__ void __launch_bounds__(kThreads) k_finish_sampled(SampledArgs a, Scal
     a.est[c] = float(e);
     if (a.raw) a.raw[c] = int64_t(r);
   }
-  a.hist[c] = 0;
   if (c == 0) {
     *a.q.tail = 0;
     *a.q.head = 0;
@@ -883,7 +886,7 @@ __global__ void __launch_bounds__(kThreads) k_sampled(SampledArgs a) {
     sample_j4(a.v, a.d, b, a.blocks[4], lut, h_lds, a.rows[4]);
   }
   __syncthreads();
-  flush(h_lds, a.hist, 256);
+  flush(h_lds, hist_copy(a.hist, kSampleHistStride), 256);
 }
 
 // Drain the work queue that k_sampled filled (without bit rows).
@@ -928,7 +931,7 @@ __global__ void __launch_bounds__(kThreads) k_sampled_drain(SampledArgs a) {
     }
   }
   __syncthreads();
-  flush(h_lds, a.hist, 256);
+  flush(h_lds, hist_copy(a.hist, kSampleHistStride), 256);
 }
 
 unsigned grid_for(uint64_t items, uint64_t per_block, unsigned cap = 512) {
@@ -1013,8 +1016,8 @@ int launch_sampled(const hm_graph* H, int k, const uint32_t* const idx[5], const
   // enqueued after this call
   a.q.job = nullptr;
   a.q.cap = 0;
-  a.q.tail = H->sample_hist + 257;
-  a.q.head = H->sample_hist + 258;
+  a.q.tail = H->sample_hist + uint64_t(kHistCopies) * kSampleHistStride + 1;
+  a.q.head = H->sample_hist + uint64_t(kHistCopies) * kSampleHistStride + 2;
   a.q.tcls = nullptr;
   const uint32_t scale = sample_chunk_scale();
   a.q.ct = std::max<uint32_t>(1, kChunkT / scale);

@@ -304,8 +304,9 @@ __global__ void __launch_bounds__(kThreads) k_sp_b4(View v, PairLinks pl, uint64
   for (uint64_t i = wave; i < n3; i += n_waves)
     b4_sparse<true>(v, pl, v.e3[3 * i], v.e3[3 * i + 1], v.e3[3 * i + 2], lut, h_main, h_sub);
   __syncthreads();
-  flush(h_main, hist + kMain, 256);
-  flush(h_sub, hist + kSub, 256);
+  unsigned long long* hc = hist_copy(hist, kExactHistStride);
+  flush(h_main, hc + kMain, 256);
+  flush(h_sub, hc + kSub, 256);
 }
 
 // Induced shape counts from the non-induced ones, into the G2 region.
