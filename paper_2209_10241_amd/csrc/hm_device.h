@@ -26,6 +26,48 @@ __device__ inline bool has3(const Set128& s, uint32_t a, uint32_t b, uint32_t c)
   sort3(a, b, c);
   return set128_has(s, key3(a, b, c));
 }
+// Membership tests split in two, so that the first probes of several keys
+// are loaded together: *_start loads the key's home slot, *_end finishes the
+// probe (further loads only after a collision).
+struct Probe64 {
+  unsigned long long key, pos, v;
+};
+struct Probe128 {
+  Key128 key;
+  unsigned long long pos;
+  ulonglong2 v;
+};
+__device__ inline Probe64 probe2_start(const Set64& s, uint32_t u, uint32_t w) {
+  Probe64 p;
+  p.key = u < w ? key2(u, w) : key2(w, u);
+  p.pos = mix64(p.key) & s.mask;
+  p.v = s.slot[p.pos];
+  return p;
+}
+__device__ inline bool probe64_end(const Set64& s, Probe64 p) {
+  while (true) {
+    if (p.v == p.key) return true;
+    if (p.v == kEmpty64) return false;
+    p.pos = (p.pos + 1) & s.mask;
+    p.v = s.slot[p.pos];
+  }
+}
+__device__ inline Probe128 probe3_start(const Set128& s, uint32_t a, uint32_t b, uint32_t c) {
+  sort3(a, b, c);
+  Probe128 p;
+  p.key = key3(a, b, c);
+  p.pos = hash128(p.key) & s.mask;
+  p.v = *reinterpret_cast<const ulonglong2*>(s.slot + 2 * p.pos);
+  return p;
+}
+__device__ inline bool probe128_end(const Set128& s, Probe128 p) {
+  while (true) {
+    if (p.v.x == p.key.hi && p.v.y == p.key.lo) return true;
+    if (p.v.x == kEmpty64) return false;
+    p.pos = (p.pos + 1) & s.mask;
+    p.v = *reinterpret_cast<const ulonglong2*>(s.slot + 2 * p.pos);
+  }
+}
 // lexicographic comparison of ascending triples
 __device__ inline bool tri_less(uint32_t a0, uint32_t a1, uint32_t a2, uint32_t b0, uint32_t b1, uint32_t b2) {
   if (a0 != b0) return a0 < b0;

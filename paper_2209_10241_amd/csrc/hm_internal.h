@@ -254,6 +254,10 @@ struct hm_graph {
   // of their hyperedge in e3; built on first use without bit rows
   unsigned long long* pl_keys = nullptr;
   uint32_t* pl_edge = nullptr;
+  // hash index over the distinct pair keys: slot = (key, start << 32 | count)
+  // of the key's run in pl_keys; pl_mask + 1 slots
+  unsigned long long* pl_slot = nullptr;
+  unsigned long long pl_mask = 0;
   // per node, built on first use without bit rows: triangles at the node, sum
   // of its neighbours' degrees, its 3-node hyperedges by pairwise pattern (8)
   unsigned long long* ns_tri = nullptr;

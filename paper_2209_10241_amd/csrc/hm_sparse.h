@@ -27,20 +27,32 @@
 namespace hm {
 
 // Pairs inside 3-node hyperedges, sorted: keys (x << 32) | y with x < y, and
-// the position in e3 of the hyperedge each came from.
+// the position in e3 of the hyperedge each came from; a hash index (linear
+// probing, slots of (key, start << 32 | count)) finds the run of one key.
 struct PairLinks {
   const unsigned long long* keys;
   const uint32_t* edge;
   uint64_t n;
+  const ulonglong2* slot;
+  unsigned long long mask;
 };
 
-__device__ inline uint64_t pl_lower(const PairLinks& pl, unsigned long long key) {
-  uint64_t lo = 0, hi = pl.n;
-  while (lo < hi) {
-    const uint64_t m = lo + ((hi - lo) >> 1);
-    if (pl.keys[m] < key) lo = m + 1; else hi = m;
+// Run [*lo, *lo + *len) of pl.keys holding `key` (empty when absent).
+__device__ inline void pl_find(const PairLinks& pl, unsigned long long key, uint64_t* lo, uint32_t* len) {
+  *lo = 0;
+  *len = 0;
+  if (!pl.n) return;
+  unsigned long long h = mix64(key) & pl.mask;
+  while (true) {
+    const ulonglong2 s = pl.slot[h];
+    if (s.x == key) {
+      *lo = s.y >> 32;
+      *len = uint32_t(s.y);
+      return;
+    }
+    if (s.x == kEmpty64) return;
+    h = (h + 1) & pl.mask;
   }
-  return lo;
 }
 
 __device__ inline uint32_t deg2_of(const View& v, uint32_t x) { return v.g2_off[x + 1] - v.g2_off[x]; }
@@ -86,12 +98,13 @@ __device__ __forceinline__ B4Ctx b4_ctx(const View& v, const PairLinks& pl, uint
   x.base_p = has2(v.hs2, a, b) | (has2(v.hs2, a, c) << 1) | (has2(v.hs2, b, c) << 2) | (1u << 3);
   const unsigned long long kab = ((unsigned long long)a << 32) | b, kac = ((unsigned long long)a << 32) | c,
                            kbc = ((unsigned long long)b << 32) | c;
-  x.lo0 = pl_lower(pl, kab);
-  x.len0 = pl_lower(pl, kab + 1) - x.lo0;
-  x.lo1 = pl_lower(pl, kac);
-  x.len1 = pl_lower(pl, kac + 1) - x.lo1;
-  x.lo2 = pl_lower(pl, kbc);
-  x.len2 = pl_lower(pl, kbc + 1) - x.lo2;
+  uint32_t l0, l1, l2;
+  pl_find(pl, kab, &x.lo0, &l0);
+  pl_find(pl, kac, &x.lo1, &l1);
+  pl_find(pl, kbc, &x.lo2, &l2);
+  x.len0 = l0;
+  x.len1 = l1;
+  x.len2 = l2;
   const uint32_t fa = v.i4_off[a + 1] - v.i4_off[a], fb = v.i4_off[b + 1] - v.i4_off[b],
                  fc = v.i4_off[c + 1] - v.i4_off[c];
   const uint32_t m4 = (fa <= fb && fa <= fc) ? a : (fb <= fc ? b : c);

@@ -263,8 +263,9 @@ __device__ inline J2Ctx j2_ctx(const View& v, const PairLinks& pl, const unsigne
   c.ds = d0 <= d1 ? d0 : d1;
   c.dO = d0 <= d1 ? d1 : d0;
   const unsigned long long key = ((unsigned long long)e0 << 32) | e1;
-  c.tlo = pl.n ? pl_lower(pl, key) : 0;
-  c.thi = pl.n ? pl_lower(pl, key + 1) : 0;
+  uint32_t nt;
+  pl_find(pl, key, &c.tlo, &nt);
+  c.thi = c.tlo + nt;
   c.any_t = c.thi > c.tlo;
   const unsigned long long te = es[i];
   c.na[0] = 0;
@@ -408,7 +409,9 @@ __device__ void j2_walk_t(const View& v, const PairLinks& pl, const J2Ctx& c, ui
 // Corrections for the 3-node hyperedges {o, y, z} with y in N(s) u T, for the
 // items [first, last) of the list N(s) then T (a node of T that is also a
 // neighbour of s taken once; each hyperedge from the smaller of y, z when both
-// qualify).
+// qualify).  What depends on y alone (y ~ s, y ~ o, y in T) is looked up once
+// per y and kept in the item's counters; each hyperedge then needs s ~ z,
+// o ~ z, y ~ z, z in T and whether {s, y, z} is a 3-node hyperedge.
 __device__ void j2_walk_r(const View& v, const PairLinks& pl, const J2Ctx& c, uint32_t first, uint32_t last,
                           J2SparseLds& L, const uint8_t* lut, unsigned long long* h) {
   const uint32_t sb = v.g2_off[c.s];
@@ -420,19 +423,38 @@ __device__ void j2_walk_r(const View& v, const PairLinks& pl, const J2Ctx& c, ui
         if (y == c.o || (j >= c.ds && has2(v.hs2, c.s, y))) return;
         const unsigned long long ky =
             y < c.o ? (((unsigned long long)y << 32) | c.o) : (((unsigned long long)c.o << 32) | y);
-        const uint64_t lo = pl_lower(pl, ky);
+        uint64_t lo;
+        pl_find(pl, ky, &lo, len);
         base[0] = uint32_t(lo);
-        len[0] = uint32_t(pl_lower(pl, ky + 1) - lo);
+        if (!*len) return;
+        // y ~ s holds exactly for the first part of the list (a node of T
+        // adjacent to s was taken there); y is in T in the second part
+        const uint32_t sy = j < c.ds, ty = j < c.ds ? uint32_t(j2_in_t(v, c, y)) : 1u;
+        const uint32_t oy = has2(v.hs2, c.o, y);
+        L.cnt[threadIdx.x][0] = y;
+        L.cnt[threadIdx.x][1] = sy | (oy << 1) | (ty << 2);
       },
       [&](uint32_t slot, uint32_t, uint32_t r) {
-        const uint32_t y = y_of(L.item[slot]);
+        const uint32_t y = L.cnt[slot][0], fy = L.cnt[slot][1];
+        const uint32_t sy = fy & 1u, oy = (fy >> 1) & 1u, ty = fy >> 2;
         const uint32_t* f = v.e3 + 3ull * pl.edge[r];
         const uint32_t z = f[0] ^ f[1] ^ f[2] ^ c.o ^ y;
-        if (z == c.s) return;                      // an {s, o, t}
-        if (z < y && j2_near_s(v, c, z)) return;   // taken from z
-        hadd(lut, h, j2_agg_pat(v, c, y, z), 1);
-        if (has3(v.hs3, c.s, y, z)) return;        // removed at s
-        j2_remove(v, c, lut, h, y, z);
+        if (z == c.s) return;   // an {s, o, t}
+        const Probe64 psz = probe2_start(v.hs2, c.s, z), poz = probe2_start(v.hs2, c.o, z),
+                      pyz = probe2_start(v.hs2, y, z);
+        const Probe128 psyz = probe3_start(v.hs3, c.s, y, z);
+        Probe128 ptz;
+        if (c.any_t) ptz = probe3_start(v.hs3, c.s, c.o, z);
+        const uint32_t sz = probe64_end(v.hs2, psz), oz = probe64_end(v.hs2, poz), yz = probe64_end(v.hs2, pyz);
+        const uint32_t tz = c.any_t && probe128_end(v.hs3, ptz);
+        if (z < y && (sz | tz)) return;   // taken from z
+        // as the histogram at o counts it (the smaller node first)
+        const uint32_t olo = y < z ? oy : oz, ohi = y < z ? oz : oy;
+        hadd(lut, h, 1u | (olo << 2) | (ohi << 5) | (yz << 7), 1);
+        if (probe128_end(v.hs3, psyz)) return;   // removed at s
+        // the pair {y, z} outside X whose set holds {o, y, z}, taken off
+        if (ty | tz) return;
+        hsub(lut, h, 1u | (sy << 1) | (oy << 2) | (sz << 4) | (oz << 5) | (yz << 7), 1);
       },
       [](uint32_t, uint32_t) {});
 }
@@ -970,6 +992,8 @@ int launch_sampled(const hm_graph* H, int k, const uint32_t* const idx[5], const
   a.pl.keys = H->pl_keys;
   a.pl.edge = H->pl_edge;
   a.pl.n = H->pl_keys ? 3 * H->n_by_size[3] : 0;
+  a.pl.slot = reinterpret_cast<const ulonglong2*>(H->pl_slot);
+  a.pl.mask = H->pl_mask;
   a.ns.tri = H->ns_tri;
   a.ns.nbr = H->ns_nbr;
   a.ns.h3 = H->ns_h3;

@@ -349,6 +349,32 @@ __global__ void k_pair_link_keys(const uint32_t* __restrict__ e3, uint64_t n3, u
   }
 }
 
+// Hash index over the runs of the sorted pair keys.  First pass: every run's
+// first position claims a slot for its key (start << 32); second pass: its
+// last position adds the count.
+__global__ void k_pl_index_starts(const unsigned long long* __restrict__ keys, uint64_t n, unsigned long long* slot,
+                                  unsigned long long mask) {
+  for (uint64_t p = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; p < n; p += uint64_t(gridDim.x) * blockDim.x) {
+    const unsigned long long key = keys[p];
+    if (p > 0 && keys[p - 1] == key) continue;
+    unsigned long long h = mix64(key) & mask;
+    while (atomicCAS(&slot[2 * h], kEmpty64, key) != kEmpty64) h = (h + 1) & mask;
+    slot[2 * h + 1] = (unsigned long long)p << 32;
+  }
+}
+
+__global__ void k_pl_index_counts(const unsigned long long* __restrict__ keys, uint64_t n, unsigned long long* slot,
+                                  unsigned long long mask) {
+  for (uint64_t p = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; p < n; p += uint64_t(gridDim.x) * blockDim.x) {
+    const unsigned long long key = keys[p];
+    if (p + 1 < n && keys[p + 1] == key) continue;
+    unsigned long long h = mix64(key) & mask;
+    while (slot[2 * h] != key) h = (h + 1) & mask;
+    const unsigned long long start = slot[2 * h + 1] >> 32;
+    slot[2 * h + 1] = (start << 32) | (p + 1 - start);
+  }
+}
+
 struct Scratch {
   std::vector<void*> ptrs;
   ~Scratch() {
@@ -524,16 +550,32 @@ int ensure_pair_links(hm_graph* H, hipStream_t st) {
   if (rc == HM_OK)
     rc = radix_sort_pairs(static_cast<unsigned long long*>(k), static_cast<uint32_t*>(e),
                           static_cast<unsigned long long*>(kt), static_cast<uint32_t*>(et), n, 32 + bits, st);
+  // the index: at most n distinct keys, load at most 1/2
+  const unsigned long long cap = pow2_capacity(n);
+  void* slots = nullptr;
+  if (rc == HM_OK) rc = dalloc(&slots, 2 * cap * sizeof(unsigned long long));
+  if (rc == HM_OK) rc = fill_u64(static_cast<unsigned long long*>(slots), kEmpty64, 2 * cap, st);
+  if (rc == HM_OK) {
+    const unsigned g = grid_cap(n, 256, 4096);
+    k_pl_index_starts<<<g, 256, 0, st>>>(static_cast<const unsigned long long*>(k), n,
+                                         static_cast<unsigned long long*>(slots), cap - 1);
+    k_pl_index_counts<<<g, 256, 0, st>>>(static_cast<const unsigned long long*>(k), n,
+                                         static_cast<unsigned long long*>(slots), cap - 1);
+    if (hipGetLastError() != hipSuccess) rc = HM_EDEVICE;
+  }
   if (rc == HM_OK && hipStreamSynchronize(st) != hipSuccess) rc = HM_EDEVICE;
   dfree(kt);
   dfree(et);
   if (rc != HM_OK) {
     dfree(k);
     dfree(e);
+    dfree(slots);
     return rc;
   }
   H->pl_keys = static_cast<unsigned long long*>(k);
   H->pl_edge = static_cast<uint32_t*>(e);
+  H->pl_slot = static_cast<unsigned long long*>(slots);
+  H->pl_mask = cap - 1;
   return HM_OK;
 }
 
@@ -542,6 +584,8 @@ PairLinks pair_links_of(const hm_graph* H) {
   pl.keys = H->pl_keys;
   pl.edge = H->pl_edge;
   pl.n = H->pl_keys ? 3 * H->n_by_size[3] : 0;
+  pl.slot = reinterpret_cast<const ulonglong2*>(H->pl_slot);
+  pl.mask = H->pl_mask;
   return pl;
 }
 
