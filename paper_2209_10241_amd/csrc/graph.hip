@@ -122,12 +122,8 @@ __global__ void k_dedup_insert(const uint32_t* __restrict__ sm, const uint64_t* 
     const unsigned long long mine = (tag << 32) | i;
     unsigned long long pos = h & mask;
     while (true) {
-      unsigned long long cur = slots[pos];
-      if (cur == kEmpty64) {
-        const unsigned long long prev = atomicCAS(&slots[pos], kEmpty64, mine);
-        if (prev == kEmpty64) break;
-        cur = prev;
-      }
+      const unsigned long long cur = atomicCAS(&slots[pos], kEmpty64, mine);
+      if (cur == kEmpty64) break;
       if ((cur >> 32) == tag && same_tuple(sm, off, size, hash, uint32_t(cur), i)) {
         atomicMin(&slots[pos], mine);
         break;
@@ -196,12 +192,19 @@ __global__ void __launch_bounds__(kTile) k_first_tiles(const uint32_t* __restric
   }
 }
 
-// Exclusive scan of the tile counters in place, and the five totals.  One
-// workgroup of 1024: thread t takes a run of consecutive tiles, the runs'
-// sums are scanned across the workgroup, and each thread then writes the
-// offsets of its run.  Every count is below 2^32 (so are the incidences).
+// What the build reads back once: validation flags and the five totals.
+struct Report {
+  DevFlags flags;
+  unsigned long long totals[kTileN];
+};
+
+// Exclusive scan of the tile counters in place; the five totals and the
+// validation flags go to the report (pinned host memory).  One workgroup of
+// 1024: thread t takes a run of consecutive tiles, the runs' sums are scanned
+// across the workgroup, and each thread then writes the offsets of its run.
+// Every count is below 2^32 (so are the incidences).
 __global__ void __launch_bounds__(1024) k_tile_scan(uint32_t* __restrict__ tile_cnt, uint64_t n_tiles,
-                                                    unsigned long long* __restrict__ totals) {
+                                                    const DevFlags* __restrict__ flags, Report* out) {
   __shared__ uint32_t wsum[kTileN][1024 / kWave];
   const uint32_t lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
   const uint64_t per = (n_tiles + 1023) / 1024;
@@ -233,8 +236,9 @@ __global__ void __launch_bounds__(1024) k_tile_scan(uint32_t* __restrict__ tile_
   }
   if (threadIdx.x == 1023) {
 #pragma unroll
-    for (int k = 0; k < kTileN; ++k) totals[k] = pre[k];
+    for (int k = 0; k < kTileN; ++k) out->totals[k] = pre[k];
   }
+  if (threadIdx.x == 0) out->flags = *flags;
 }
 
 // Write the unique hyperedges out, in first-occurrence order, with everything
@@ -340,39 +344,36 @@ __global__ void k_multi_fill(FillRegions r) {
 
 // Exclusive scans of the three degree arrays (n nodes x R copies) into row
 // offsets o[v] = (scan at v * R), n + 1 entries, and, for the incidence lists,
-// fill cursors c of every (node, copy).  One workgroup of 1024 per array.
+// fill cursors c of every (node, copy).  One workgroup of 1024 per array:
+// thread t takes a run of consecutive counters, the runs' sums are scanned
+// across the workgroup, and each thread then writes the results of its run.
 __global__ void __launch_bounds__(1024) k_scan_degrees(const uint32_t* __restrict__ d0, uint32_t* __restrict__ o0,
                                                        const uint32_t* __restrict__ d1, uint32_t* __restrict__ o1,
                                                        uint32_t* __restrict__ c1, const uint32_t* __restrict__ d2,
                                                        uint32_t* __restrict__ o2, uint32_t* __restrict__ c2, uint32_t n,
                                                        uint32_t R) {
   __shared__ uint32_t wsum[1024 / kWave];
-  __shared__ uint32_t carry;
   const uint32_t* d = blockIdx.x == 0 ? d0 : blockIdx.x == 1 ? d1 : d2;
   uint32_t* o = blockIdx.x == 0 ? o0 : blockIdx.x == 1 ? o1 : o2;
   uint32_t* c = blockIdx.x == 0 ? nullptr : blockIdx.x == 1 ? c1 : c2;
   const uint32_t lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
   const uint32_t m = n * R;
-  if (threadIdx.x == 0) carry = 0;
+  const uint32_t per = (m + 1023) / 1024;
+  const uint32_t t0 = min(m, threadIdx.x * per), t1 = min(m, t0 + per);
+  uint32_t sum = 0;
+  for (uint32_t t = t0; t < t1; ++t) sum += d[t];
+  uint32_t tot;
+  uint32_t pre = wave_exclusive_scan(sum, &tot);
+  if (lane == 0) wsum[wv] = tot;
   __syncthreads();
-  for (uint32_t c0 = 0; c0 < m; c0 += 1024) {
-    const uint32_t t = c0 + threadIdx.x;
-    const uint32_t x = t < m ? d[t] : 0;
-    uint32_t tot;
-    const uint32_t ex = wave_exclusive_scan(x, &tot);
-    if (lane == 0) wsum[wv] = tot;
-    __syncthreads();
-    uint32_t before = carry;
-    for (uint32_t q = 0; q < wv; ++q) before += wsum[q];
-    if (t < m) {
-      if (c) c[t] = before + ex;
-      if ((t & (R - 1)) == 0) o[t / R] = before + ex;
-    }
-    __syncthreads();
-    if (threadIdx.x == 1023) carry = before + ex + x;
-    __syncthreads();
+  for (uint32_t q = 0; q < wv; ++q) pre += wsum[q];
+  for (uint32_t t = t0; t < t1; ++t) {
+    const uint32_t x = d[t];
+    if (c) c[t] = pre;
+    if ((t & (R - 1)) == 0) o[t / R] = pre;
+    pre += x;
   }
-  if (threadIdx.x == 0) o[n] = carry;
+  if (threadIdx.x == 1023) o[n] = pre;
 }
 
 // Row offsets o[v] = s[v * R] for v = 0..n from scans s of n * R + 1 entries
@@ -389,12 +390,14 @@ __global__ void k_offsets_of_copies(const uint32_t* __restrict__ s0, uint32_t* _
 }
 
 // Sorted pairwise rows read off the adjacency bit rows: one wavefront per
-// node, 64 words at a time, set bits written in ascending order.
-__global__ void k_rows_from_bits(const uint32_t* __restrict__ bits, uint32_t n, uint32_t W,
-                                 const uint32_t* __restrict__ row_off, uint32_t* __restrict__ adj) {
+// node, 64 words at a time, set bits written in ascending order (workgroup
+// `block` of `n_blocks`).
+__device__ void rows_from_bits(const uint32_t* __restrict__ bits, uint32_t n, uint32_t W,
+                               const uint32_t* __restrict__ row_off, uint32_t* __restrict__ adj, uint32_t block,
+                               uint32_t n_blocks) {
   const uint32_t lane = threadIdx.x & (kWave - 1);
-  const uint64_t wave = (uint64_t(blockIdx.x) * blockDim.x + threadIdx.x) / kWave;
-  const uint64_t n_waves = uint64_t(gridDim.x) * blockDim.x / kWave;
+  const uint64_t wave = (uint64_t(block) * blockDim.x + threadIdx.x) / kWave;
+  const uint64_t n_waves = uint64_t(n_blocks) * blockDim.x / kWave;
   for (uint64_t x = wave; x < n; x += n_waves) {
     uint32_t base = row_off[x];
     const uint32_t* row = bits + x * W;
@@ -413,11 +416,11 @@ __global__ void k_rows_from_bits(const uint32_t* __restrict__ bits, uint32_t n, 
 
 // Incidence lists of the 3- and 4-node hyperedges (positions in any order):
 // hyperedge i fills through the cursor of copy i & (R - 1) of each member,
-// the copy its degree was counted in.
-__global__ void k_inc_fill(const uint32_t* __restrict__ e3, uint64_t n3, uint32_t* cur3, uint32_t* idx3,
-                           const uint32_t* __restrict__ e4, uint64_t n4, uint32_t* cur4, uint32_t* idx4, uint32_t R) {
-  for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n3 + n4;
-       i += uint64_t(gridDim.x) * blockDim.x) {
+// the copy its degree was counted in (workgroup `block` of `n_blocks`).
+__device__ void inc_fill(const uint32_t* __restrict__ e3, uint64_t n3, uint32_t* cur3, uint32_t* idx3,
+                         const uint32_t* __restrict__ e4, uint64_t n4, uint32_t* cur4, uint32_t* idx4, uint32_t R,
+                         uint32_t block, uint32_t n_blocks) {
+  for (uint64_t i = uint64_t(block) * blockDim.x + threadIdx.x; i < n3 + n4; i += uint64_t(n_blocks) * blockDim.x) {
     if (i < n3) {
       const uint32_t cp = uint32_t(i) & (R - 1);
       for (int j = 0; j < 3; ++j) idx3[atomicAdd(&cur3[uint64_t(e3[3 * i + j]) * R + cp], 1u)] = uint32_t(i);
@@ -427,6 +430,24 @@ __global__ void k_inc_fill(const uint32_t* __restrict__ e3, uint64_t n3, uint32_
       for (int j = 0; j < 4; ++j) idx4[atomicAdd(&cur4[uint64_t(e4[4 * q + j]) * R + cp], 1u)] = uint32_t(q);
     }
   }
+}
+
+__global__ void k_inc_fill(const uint32_t* __restrict__ e3, uint64_t n3, uint32_t* cur3, uint32_t* idx3,
+                           const uint32_t* __restrict__ e4, uint64_t n4, uint32_t* cur4, uint32_t* idx4, uint32_t R) {
+  inc_fill(e3, n3, cur3, idx3, e4, n4, cur4, idx4, R, blockIdx.x, gridDim.x);
+}
+
+// Pairwise rows from the bit rows (workgroups [0, row_blocks)) and the
+// incidence lists (the rest) in one launch.
+__global__ void k_rows_and_incidence(const uint32_t* __restrict__ bits, uint32_t n, uint32_t W,
+                                     const uint32_t* __restrict__ row_off, uint32_t* __restrict__ adj,
+                                     uint32_t row_blocks, const uint32_t* __restrict__ e3, uint64_t n3, uint32_t* cur3,
+                                     uint32_t* idx3, const uint32_t* __restrict__ e4, uint64_t n4, uint32_t* cur4,
+                                     uint32_t* idx4, uint32_t R) {
+  if (blockIdx.x < row_blocks)
+    rows_from_bits(bits, n, W, row_off, adj, blockIdx.x, row_blocks);
+  else
+    inc_fill(e3, n3, cur3, idx3, e4, n4, cur4, idx4, R, blockIdx.x - row_blocks, gridDim.x - row_blocks);
 }
 
 __global__ void k_pair_keys(const uint32_t* __restrict__ e2, uint64_t n, int bits_per_node,
@@ -492,13 +513,8 @@ uint32_t degree_copies(uint64_t n_nodes) {
   return R;
 }
 
-// What the build reads back once: validation flags and the five totals.  It
-// lands in pinned host memory, taken from a pool kept for the process.
-struct Report {
-  DevFlags flags;
-  unsigned long long totals[kTileN];
-};
-static_assert(sizeof(Report) % 8 == 0, "report is cleared as 64-bit words");
+// The report lands in pinned host memory, taken from a pool kept for the
+// process.
 
 std::mutex g_report_mu;
 std::vector<Report*> g_report_pool;
@@ -551,12 +567,12 @@ int build(hm_graph* H, const uint32_t* members_in, const uint64_t* offsets_in, u
   }
   const uint64_t E = n_edges;
   const uint64_t n_tiles = (E + kTile - 1) / kTile;
-  Report* report = nullptr;
+  DevFlags* flags = nullptr;
   uint32_t *sm = nullptr, *size = nullptr, *tile_cnt = nullptr;
   unsigned long long *hash = nullptr, *slots = nullptr, *slot_of = nullptr;
   uint8_t* first = nullptr;
   const unsigned long long cap = pow2_capacity(E);
-  HM_TRY(tmp.get(&report, 1));
+  HM_TRY(tmp.get(&flags, 1));
   HM_TRY(tmp.get(&sm, n_members));
   HM_TRY(tmp.get(&size, E));
   HM_TRY(tmp.get(&hash, E));
@@ -564,14 +580,18 @@ int build(hm_graph* H, const uint32_t* members_in, const uint64_t* offsets_in, u
   HM_TRY(tmp.get(&slot_of, E));
   HM_TRY(tmp.get(&first, E));
   HM_TRY(tmp.get(&tile_cnt, n_tiles * kTileN));
-  DevFlags* flags = &report->flags;
+  static_assert(sizeof(DevFlags) % 8 == 0, "flags are cleared as 64-bit words");
+  PinnedReport rep;
+  HM_TRY(rep.take());
+  Report* rep_dev = nullptr;
+  HM_HIP(hipHostGetDevicePointer(reinterpret_cast<void**>(&rep_dev), rep.p, 0));
   {
     FillRegions r{};
-    r.ptr[0] = report;
-    r.count[0] = sizeof(Report) / 8;
+    r.ptr[0] = flags;
+    r.count[0] = sizeof(DevFlags) / 8;
     r.value[0] = 0;
     r.wide[0] = 1;
-    r.ptr[1] = &report->flags.err_edge;   // no offending hyperedge yet
+    r.ptr[1] = &flags->err_edge;   // no offending hyperedge yet
     r.count[1] = 1;
     r.value[1] = 0xFFFFFFFFu;
     r.wide[1] = 0;
@@ -587,12 +607,11 @@ int build(hm_graph* H, const uint32_t* members_in, const uint64_t* offsets_in, u
     k_prepare<<<grid_for(E), 256, 0, st>>>(members, offsets, E, n_members, H->n_nodes, sm, size, hash, flags);
     k_dedup_insert<<<grid_for(E), 256, 0, st>>>(sm, offsets, size, hash, E, slots, cap - 1, slot_of);
     k_first_tiles<<<unsigned(n_tiles), kTile, 0, st>>>(size, E, slots, slot_of, first, tile_cnt, flags);
-    k_tile_scan<<<1, 1024, 0, st>>>(tile_cnt, n_tiles, report->totals);
+    k_tile_scan<<<1, 1024, 0, st>>>(tile_cnt, n_tiles, flags, rep_dev);
     HM_HIP(hipGetLastError());
+  } else {
+    *rep.p = Report{};
   }
-  PinnedReport rep;
-  HM_TRY(rep.take());
-  HM_HIP(hipMemcpyAsync(rep.p, report, sizeof(Report), hipMemcpyDeviceToHost, st));
   HM_HIP(hipStreamSynchronize(st));
   const DevFlags got = rep.p->flags;
   unsigned long long tot[kTileN];
@@ -710,32 +729,34 @@ int build(hm_graph* H, const uint32_t* members_in, const uint64_t* offsets_in, u
                                                          uint32_t(N), R);
     HM_HIP(hipGetLastError());
   }
-  if (n3 + n4) {
+  if (keep_bits && (n2 || n3 + n4)) {
+    // ascending rows straight from the bit rows, and the incidence lists
+    const uint32_t row_blocks = n2 ? grid_for(N * kWave) : 0;
+    const uint32_t inc_blocks = (n3 + n4) ? grid_for(n3 + n4) : 0;
+    k_rows_and_incidence<<<row_blocks + inc_blocks, 256, 0, st>>>(H->bits, uint32_t(N), H->words, H->g2_off,
+                                                                  H->g2_adj, row_blocks, H->e3, n3, cur3, H->i3_idx,
+                                                                  H->e4, n4, cur4, H->i4_idx, R);
+    HM_HIP(hipGetLastError());
+  } else if (n3 + n4) {
     k_inc_fill<<<grid_for(n3 + n4), 256, 0, st>>>(H->e3, n3, cur3, H->i3_idx, H->e4, n4, cur4, H->i4_idx, R);
     HM_HIP(hipGetLastError());
   }
-  if (n2) {
-    if (keep_bits) {
-      // ascending rows straight from the bit rows
-      k_rows_from_bits<<<grid_for(N * kWave), 256, 0, st>>>(H->bits, uint32_t(N), H->words, H->g2_off, H->g2_adj);
-      HM_HIP(hipGetLastError());
-    } else {
-      // ascending rows from a radix sort of directed pairs, with the position
-      // in e2 of each entry's pair
-      const int B = node_bits(H->n_nodes);
-      const uint64_t m = 2 * n2;
-      unsigned long long *keys, *keys_tmp;
-      uint32_t* vals_tmp;
-      HM_TRY(tmp.get(&keys, m));
-      HM_TRY(tmp.get(&keys_tmp, m));
-      HM_TRY(tmp.get(&vals_tmp, m));
-      HM_TRY(owned(&H->g2_eid, m));
-      k_pair_keys<<<grid_for(n2), 256, 0, st>>>(H->e2, n2, B, keys, H->g2_eid);
-      HM_HIP(hipGetLastError());
-      HM_TRY(radix_sort_pairs(keys, H->g2_eid, keys_tmp, vals_tmp, m, 2 * B, st));
-      k_pair_adj<<<grid_for(m), 256, 0, st>>>(keys, m, (1ull << B) - 1, H->g2_adj);
-      HM_HIP(hipGetLastError());
-    }
+  if (n2 && !keep_bits) {
+    // ascending rows from a radix sort of directed pairs, with the position
+    // in e2 of each entry's pair
+    const int B = node_bits(H->n_nodes);
+    const uint64_t m = 2 * n2;
+    unsigned long long *keys, *keys_tmp;
+    uint32_t* vals_tmp;
+    HM_TRY(tmp.get(&keys, m));
+    HM_TRY(tmp.get(&keys_tmp, m));
+    HM_TRY(tmp.get(&vals_tmp, m));
+    HM_TRY(owned(&H->g2_eid, m));
+    k_pair_keys<<<grid_for(n2), 256, 0, st>>>(H->e2, n2, B, keys, H->g2_eid);
+    HM_HIP(hipGetLastError());
+    HM_TRY(radix_sort_pairs(keys, H->g2_eid, keys_tmp, vals_tmp, m, 2 * B, st));
+    k_pair_adj<<<grid_for(m), 256, 0, st>>>(keys, m, (1ull << B) - 1, H->g2_adj);
+    HM_HIP(hipGetLastError());
   }
   // no wait: later calls on the stream are ordered after the build, and the
   // temporaries return to the cache only once it has run
