@@ -49,6 +49,19 @@ __device__ inline unsigned long long* row_or(unsigned long long* rows, uint64_t 
   return rows ? rows + s * 256 : h;
 }
 
+// Per-sample-row mode without bit rows: a sample's (or a queued job's) counts
+// gather in LDS and reach its row in device memory once, at the end, by the
+// threads [t0, t0 + n) that worked on it (which then clear the LDS copy).
+__device__ inline void flush_row(unsigned long long* h, unsigned long long* row, uint32_t t, uint32_t n) {
+  for (uint32_t c = t; c < 256; c += n) {
+    const unsigned long long x = h[c];
+    if (x) {
+      atomicAdd(&row[c], x);
+      h[c] = 0;
+    }
+  }
+}
+
 // j = 4: the sampled 4-node hyperedge is the only candidate set.  One thread
 // per sample.
 __device__ void sample_j4(const View& v, const Draws& d, uint32_t part, uint32_t n_parts, const uint8_t* lut,
@@ -119,16 +132,18 @@ __device__ __forceinline__ void j3_exceptions(const View& v, const PairLinks& pl
 }
 
 template <bool BITS>
+// hw: without bit rows in per-sample-row mode, 256 counters of LDS per
+// wavefront (zero on entry, left zero) in which each sample's counts gather.
 __device__ void sample_j3_k4(const View& v, const PairLinks& pl, const Queue& q, const Draws& d, uint32_t part,
                              uint32_t n_parts, uint32_t* sets, const uint8_t* lut, unsigned long long* h_lds,
-                             unsigned long long* rows) {
+                             unsigned long long* rows, unsigned long long (*hw)[256]) {
   const int wv = threadIdx.x / kWave;
   const uint32_t lane = threadIdx.x & (kWave - 1);
   for (uint64_t s = uint64_t(part) * kWavesPerBlock + wv; s < d.S[3]; s += uint64_t(n_parts) * kWavesPerBlock) {
     const uint64_t i = d.at(3, s);
     if (i >= d.n[3]) continue;
     const uint32_t a = v.e3[3 * i], b = v.e3[3 * i + 1], c = v.e3[3 * i + 2];
-    unsigned long long* h = row_or(rows, s, h_lds);
+    unsigned long long* h = (!BITS && rows) ? hw[wv] : row_or(rows, s, h_lds);
     if constexpr (BITS) {
       b4_edge_bits_count<false>(a, b, c, v.e3, v.e4, v.i3_off, v.i3_idx, v.i4_off, v.i4_idx, v.bits, v.W, sets + wv * b4_set_words(v.W),
                                 lut, h, nullptr);
@@ -153,6 +168,11 @@ __device__ void sample_j3_k4(const View& v, const PairLinks& pl, const Queue& q,
         for (uint64_t k = lane; k < jobs; k += kWave)
           q.job[base + k] = make_uint4(kJobTriple, uint32_t(s), uint32_t(k * q.cx),
                                        uint32_t(min<uint64_t>((k + 1) * q.cx, x.total)));
+      }
+      if (rows) {
+        wave_sync();
+        flush_row(h, rows + s * 256, lane, kWave);
+        wave_sync();
       }
     }
   }
@@ -504,7 +524,7 @@ __device__ void sample_j2_k4_sparse(const View& v, const PairLinks& pl, const No
   for (uint64_t smp = part; smp < d.S[2]; smp += n_parts) {
     const uint64_t i = d.at(2, smp);
     if (i >= d.n[2]) continue;
-    unsigned long long* h = row_or(rows, smp, h_lds);
+    unsigned long long* h = h_lds;   // in per-sample-row mode, flushed to the row below
     const J2Ctx c = j2_ctx(v, pl, es, d.n[2], i);
     const uint32_t s = c.s, o = c.o, ds = c.ds, dO = c.dO;
     const uint32_t n_t = uint32_t(c.thi - c.tlo);
@@ -603,6 +623,10 @@ __device__ void sample_j2_k4_sparse(const View& v, const PairLinks& pl, const No
       j2_walk_r(v, pl, c, 0, n_r, L, lut, h);
     }
     __syncthreads();
+    if (rows) {
+      flush_row(h_lds, rows + smp * 256, tid, kThreads);
+      __syncthreads();
+    }
   }
 }
 
@@ -847,7 +871,10 @@ struct SampledLds<4, true> {
 };
 template <>
 struct SampledLds<4, false> {
-  J2SparseLds j2;
+  union {
+    J2SparseLds j2;
+    unsigned long long hw[kWavesPerBlock][256];   // per-sample counters of the 3-node samples (row mode)
+  };
 };
 
 // After the sampler (and its queue's drain): scale the raw counts in a.hist
@@ -898,9 +925,15 @@ __global__ void __launch_bounds__(kThreads) k_sampled(SampledArgs a) {
       sample_j2_k3(a.v, a.d, b, a.blocks[2], lut, h_lds, a.rows[2]);
   } else if ((b -= a.blocks[2]) < a.blocks[3]) {
     if constexpr (K == 4 && BITS)
-      sample_j3_k4<true>(a.v, a.pl, a.q, a.d, b, a.blocks[3], lds.b4, lut, h_lds, a.rows[3]);
-    else if constexpr (K == 4)
-      sample_j3_k4<false>(a.v, a.pl, a.q, a.d, b, a.blocks[3], nullptr, lut, h_lds, a.rows[3]);
+      sample_j3_k4<true>(a.v, a.pl, a.q, a.d, b, a.blocks[3], lds.b4, lut, h_lds, a.rows[3], nullptr);
+    else if constexpr (K == 4) {
+      if (a.rows[3]) {
+        const uint32_t lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+        for (uint32_t c = lane; c < 256; c += kWave) lds.hw[wv][c] = 0;
+        wave_sync();
+      }
+      sample_j3_k4<false>(a.v, a.pl, a.q, a.d, b, a.blocks[3], nullptr, lut, h_lds, a.rows[3], lds.hw);
+    }
     else
       sample_j3_k3(a.v, a.d, b, a.blocks[3], lut, h_lds, a.rows[3]);
   } else if (K == 4) {
@@ -930,15 +963,19 @@ __global__ void __launch_bounds__(kThreads) k_sampled_drain(SampledArgs a) {
     __syncthreads();
     const uint4 jb = job;
     if (jb.x == 0xFFFFFFFFu) break;
+    // counts gather in h_lds; in per-sample-row mode each job's go to its
+    // sample's row at the end of the job
+    unsigned long long* h = h_lds;
+    unsigned long long* row = nullptr;
     if (jb.x == kJobPairS || jb.x == kJobPairQ) {
       const J2Ctx c = j2_ctx(a.v, a.pl, a.es, a.d.n[2], a.d.at(2, jb.y));
-      unsigned long long* h = row_or(a.rows[2], jb.y, h_lds);
+      if (a.rows[2]) row = a.rows[2] + uint64_t(jb.y) * 256;
       if (jb.x == kJobPairS) j2_pass_s(a.v, c, jb.z, jb.w, threadIdx.x, kThreads, lut, h);
       else j2_pass_q(a.v, c, jb.z, jb.w, threadIdx.x, kThreads, lut, h);
     } else if (jb.x == kJobPairT || jb.x == kJobPairR) {
       const uint64_t i = a.d.at(2, jb.y);
       const J2Ctx c = j2_ctx(a.v, a.pl, a.es, a.d.n[2], i);
-      unsigned long long* h = row_or(a.rows[2], jb.y, h_lds);
+      if (a.rows[2]) row = a.rows[2] + uint64_t(jb.y) * 256;
       if (jb.x == kJobPairT) {
         if (threadIdx.x < 3) tcls[threadIdx.x] = a.q.tcls[3ull * jb.y + threadIdx.x];
         __syncthreads();
@@ -949,7 +986,12 @@ __global__ void __launch_bounds__(kThreads) k_sampled_drain(SampledArgs a) {
     } else if (jb.x == kJobTriple) {
       const uint64_t i = a.d.at(3, jb.y);
       const B4Ctx x = b4_ctx(a.v, a.pl, a.v.e3[3 * i], a.v.e3[3 * i + 1], a.v.e3[3 * i + 2]);
-      j3_exceptions(a.v, a.pl, x, jb.z, jb.w, threadIdx.x, kThreads, lut, row_or(a.rows[3], jb.y, h_lds));
+      if (a.rows[3]) row = a.rows[3] + uint64_t(jb.y) * 256;
+      j3_exceptions(a.v, a.pl, x, jb.z, jb.w, threadIdx.x, kThreads, lut, h);
+    }
+    if (row) {
+      __syncthreads();
+      flush_row(h_lds, row, threadIdx.x, kThreads);
     }
   }
   __syncthreads();
