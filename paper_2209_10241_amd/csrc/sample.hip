@@ -89,10 +89,14 @@ __device__ void sample_j4(const View& v, const Draws& d, uint32_t part, uint32_t
 // workgroup of a second launch so that one sample's work spreads over many.
 enum : uint32_t { kJobNone = 0, kJobPairT = 1, kJobPairR = 2, kJobTriple = 3, kJobPairS = 4, kJobPairQ = 5 };
 // default chunk sizes (divided by the HM_OPT_SAMPLE_CHUNK_SCALE option)
-constexpr uint32_t kChunkT = 64;    // nodes of T per chunk
-constexpr uint32_t kChunkR = 256;   // correction items per chunk
-constexpr uint32_t kChunkX = 512;   // exception positions per chunk
-constexpr uint32_t kChunkH = 1024;  // hyperedges at s (3-node) or holding e (4-node) per chunk
+constexpr uint32_t kChunkT = 4;    // nodes of T per chunk
+constexpr uint32_t kChunkR = 16;   // correction items per chunk
+constexpr uint32_t kChunkX = 32;   // exception positions per chunk
+constexpr uint32_t kChunkH = 64;   // hyperedges at s (3-node) or holding e (4-node) per chunk
+// queue entries per sample of strata 2 and 3 (times the chunk option), at
+// most kQueueMax in all; work that finds the queue full is done in place
+constexpr uint64_t kQueuePerSample = 512;
+constexpr uint64_t kQueueMax = 1ull << 26;
 
 struct Queue {
   uint4* job;                   // {kind, sample, first, last}
@@ -1098,7 +1102,7 @@ int launch_sampled(const hm_graph* H, int k, const uint32_t* const idx[5], const
     }
   } rel;
   if (k == 4 && !bits) {
-    a.q.cap = 32ull * scale * (a.d.S[2] + a.d.S[3]) + 65536;
+    a.q.cap = std::min<uint64_t>(kQueuePerSample * scale * (a.d.S[2] + a.d.S[3]) + 65536, kQueueMax);
     HM_TRY(dalloc(&rel.p[0], a.q.cap * sizeof(uint4)));
     HM_TRY(dalloc(&rel.p[1], (3 * a.d.S[2] + 1) * sizeof(uint32_t)));
     a.q.job = static_cast<uint4*>(rel.p[0]);
