@@ -300,9 +300,18 @@ int count_sampled_weighted_indices(const hm_graph* H, int k, const uint32_t* idx
  *                            (default 1, range 1..1024), so larger values
  *                            route more of the work through the queue.  The
  *                            results do not depend on it.
+ *   HM_OPT_ONE_PASS_MAX_EDGES graphs that keep bit rows and have at most this
+ *                            many input hyperedges (default and maximum
+ *                            2^20) are built in one pass: buffers are sized
+ *                            by upper bounds and hm_graph_create waits for
+ *                            the device once, at the end of the build; larger
+ *                            graphs wait once the sizes are known and are
+ *                            sized exactly.  0 builds every graph the second
+ *                            way.  The graph does not depend on it.
  * HM_EINVAL for an unknown option or a value out of range. */
 #define HM_OPT_BITSET_MAX_NODES 1
 #define HM_OPT_SAMPLE_CHUNK_SCALE 2
+#define HM_OPT_ONE_PASS_MAX_EDGES 3
 int hm_set_option(int option, int64_t value);
 int hm_get_option(int option, int64_t* value);
 

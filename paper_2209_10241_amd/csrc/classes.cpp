@@ -139,6 +139,8 @@ const char* last_error() { return g_err; }
 uint32_t bitset_max_nodes() { return g_bitset_max_nodes.load(); }
 std::atomic<uint32_t> g_sample_chunk_scale{1};
 uint32_t sample_chunk_scale() { return g_sample_chunk_scale.load(); }
+std::atomic<uint64_t> g_one_pass_max_edges{kOnePassMaxEdges};
+uint64_t one_pass_max_edges() { return g_one_pass_max_edges.load(); }
 
 const ClassTables& class_tables() {
   static const ClassTables t = build();
@@ -332,6 +334,14 @@ int hm_set_option(int option, int64_t value) {
     hm::g_sample_chunk_scale.store(uint32_t(value));
     return HM_OK;
   }
+  if (option == HM_OPT_ONE_PASS_MAX_EDGES) {
+    if (value < 0 || value > int64_t(hm::kOnePassMaxEdges)) {
+      hm::set_error("HM_OPT_ONE_PASS_MAX_EDGES must be in [0, %llu]", (unsigned long long)hm::kOnePassMaxEdges);
+      return HM_EINVAL;
+    }
+    hm::g_one_pass_max_edges.store(uint64_t(value));
+    return HM_OK;
+  }
   hm::set_error("unknown option %d", option);
   return HM_EINVAL;
 }
@@ -347,6 +357,10 @@ int hm_get_option(int option, int64_t* value) {
   }
   if (option == HM_OPT_SAMPLE_CHUNK_SCALE) {
     *value = hm::g_sample_chunk_scale.load();
+    return HM_OK;
+  }
+  if (option == HM_OPT_ONE_PASS_MAX_EDGES) {
+    *value = int64_t(hm::g_one_pass_max_edges.load());
     return HM_OK;
   }
   hm::set_error("unknown option %d", option);

@@ -199,12 +199,14 @@ struct Report {
 };
 
 // Exclusive scan of the tile counters in place; the five totals and the
-// validation flags go to the report (pinned host memory).  One workgroup of
+// validation flags go to the report (pinned host memory), the totals also to
+// dev_totals for the kernels that follow.  One workgroup of
 // 1024: thread t takes a run of consecutive tiles, the runs' sums are scanned
 // across the workgroup, and each thread then writes the offsets of its run.
 // Every count is below 2^32 (so are the incidences).
 __global__ void __launch_bounds__(1024) k_tile_scan(uint32_t* __restrict__ tile_cnt, uint64_t n_tiles,
-                                                    const DevFlags* __restrict__ flags, Report* out) {
+                                                    const DevFlags* __restrict__ flags, Report* out,
+                                                    unsigned long long* __restrict__ dev_totals) {
   __shared__ uint32_t wsum[kTileN][1024 / kWave];
   const uint32_t lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
   const uint64_t per = (n_tiles + 1023) / 1024;
@@ -236,7 +238,10 @@ __global__ void __launch_bounds__(1024) k_tile_scan(uint32_t* __restrict__ tile_
   }
   if (threadIdx.x == 1023) {
 #pragma unroll
-    for (int k = 0; k < kTileN; ++k) out->totals[k] = pre[k];
+    for (int k = 0; k < kTileN; ++k) {
+      out->totals[k] = pre[k];
+      dev_totals[k] = pre[k];
+    }
   }
   if (threadIdx.x == 0) out->flags = *flags;
 }
@@ -258,7 +263,8 @@ struct GatherOut {
   // that no counter takes more than about 1/R of its node's incidences
   uint32_t *deg2, *deg3, *deg4;
   uint32_t R;
-  unsigned long long n_unique, n_members;
+  const unsigned long long* totals;   // the five totals of k_tile_scan
+  const DevFlags* flags;              // nothing is written when the input is invalid
 };
 
 __global__ void __launch_bounds__(kTile) k_gather_tiles(const uint32_t* __restrict__ sm,
@@ -268,6 +274,7 @@ __global__ void __launch_bounds__(kTile) k_gather_tiles(const uint32_t* __restri
                                                          const uint32_t* __restrict__ tile_off,
                                                          GatherOut g) {
   __shared__ uint32_t part[kTileN][kTile / kWave];
+  if (g.flags->err) return;
   const uint64_t i = uint64_t(blockIdx.x) * kTile + threadIdx.x;
   uint32_t first = 0, s = 0;
   if (i < n_edges) {
@@ -294,7 +301,8 @@ __global__ void __launch_bounds__(kTile) k_gather_tiles(const uint32_t* __restri
   const uint32_t* m = sm + off[i];
   for (uint32_t j = 0; j < s; ++j) g.all_members[pos[4] + j] = m[j];
   g.all_off[pos[0]] = pos[4];
-  if (pos[0] + 1 == g.n_unique) g.all_off[g.n_unique] = g.n_members;
+  const unsigned long long n_unique = g.totals[0];
+  if (pos[0] + 1 == n_unique) g.all_off[n_unique] = g.totals[4];
   if (s == 2) {
     const uint32_t a = m[0], b = m[1];
     g.e2[2 * pos[1]] = a;
@@ -323,12 +331,12 @@ __global__ void __launch_bounds__(kTile) k_gather_tiles(const uint32_t* __restri
   }
 }
 
-// Up to ten fills in one launch.
+// Up to sixteen fills in one launch.
 struct FillRegions {
-  void* ptr[10];
-  unsigned long long count[10];
-  unsigned long long value[10];
-  uint32_t wide[10];   // 1: 64-bit elements, 0: 32-bit
+  void* ptr[16];
+  unsigned long long count[16];
+  unsigned long long value[16];
+  uint32_t wide[16];   // 1: 64-bit elements, 0: 32-bit
   uint32_t n;
 };
 
@@ -432,22 +440,29 @@ __device__ void inc_fill(const uint32_t* __restrict__ e3, uint64_t n3, uint32_t*
   }
 }
 
-__global__ void k_inc_fill(const uint32_t* __restrict__ e3, uint64_t n3, uint32_t* cur3, uint32_t* idx3,
-                           const uint32_t* __restrict__ e4, uint64_t n4, uint32_t* cur4, uint32_t* idx4, uint32_t R) {
-  inc_fill(e3, n3, cur3, idx3, e4, n4, cur4, idx4, R, blockIdx.x, gridDim.x);
+// (the counts of 3- and 4-node hyperedges are totals[2] and totals[3] of
+// k_tile_scan; nothing is written when the input is invalid)
+__global__ void k_inc_fill(const uint32_t* __restrict__ e3, uint32_t* cur3, uint32_t* idx3,
+                           const uint32_t* __restrict__ e4, uint32_t* cur4, uint32_t* idx4, uint32_t R,
+                           const unsigned long long* __restrict__ totals, const DevFlags* __restrict__ flags) {
+  if (flags->err) return;
+  inc_fill(e3, totals[2], cur3, idx3, e4, totals[3], cur4, idx4, R, blockIdx.x, gridDim.x);
 }
 
 // Pairwise rows from the bit rows (workgroups [0, row_blocks)) and the
 // incidence lists (the rest) in one launch.
 __global__ void k_rows_and_incidence(const uint32_t* __restrict__ bits, uint32_t n, uint32_t W,
                                      const uint32_t* __restrict__ row_off, uint32_t* __restrict__ adj,
-                                     uint32_t row_blocks, const uint32_t* __restrict__ e3, uint64_t n3, uint32_t* cur3,
-                                     uint32_t* idx3, const uint32_t* __restrict__ e4, uint64_t n4, uint32_t* cur4,
-                                     uint32_t* idx4, uint32_t R) {
+                                     uint32_t row_blocks, const uint32_t* __restrict__ e3, uint32_t* cur3,
+                                     uint32_t* idx3, const uint32_t* __restrict__ e4, uint32_t* cur4, uint32_t* idx4,
+                                     uint32_t R, const unsigned long long* __restrict__ totals,
+                                     const DevFlags* __restrict__ flags) {
+  if (flags->err) return;
   if (blockIdx.x < row_blocks)
     rows_from_bits(bits, n, W, row_off, adj, blockIdx.x, row_blocks);
   else
-    inc_fill(e3, n3, cur3, idx3, e4, n4, cur4, idx4, R, blockIdx.x - row_blocks, gridDim.x - row_blocks);
+    inc_fill(e3, totals[2], cur3, idx3, e4, totals[3], cur4, idx4, R, blockIdx.x - row_blocks,
+             gridDim.x - row_blocks);
 }
 
 __global__ void k_pair_keys(const uint32_t* __restrict__ e2, uint64_t n, int bits_per_node,
@@ -546,6 +561,30 @@ struct PinnedReport {
   }
 };
 
+// Fills gathered into one launch.
+struct FillList {
+  FillRegions r{};
+  void add(void* p, unsigned long long n, unsigned long long v, uint32_t wide) {
+    r.ptr[r.n] = p;
+    r.count[r.n] = n;
+    r.value[r.n] = v;
+    r.wide[r.n] = wide;
+    ++r.n;
+  }
+  void launch(hipStream_t st) {
+    unsigned long long most = 0;
+    for (uint32_t k = 0; k < r.n; ++k) most = std::max(most, r.count[k]);
+    k_multi_fill<<<grid_for(most), 256, 0, st>>>(r);
+  }
+};
+
+// The build.  Graphs that keep bit rows and have at most one_pass_max_edges()
+// input hyperedges are built in one pass: every buffer whose size depends on
+// the unique counts is sized by an upper bound (E per stratum, the hash sets
+// by E), all kernels are enqueued, and the host waits once at the end.  Other
+// graphs wait after the counting pass and size everything exactly.  Kernels
+// after validation read the counts from the device and do nothing when the
+// input is invalid.
 int build(hm_graph* H, const uint32_t* members_in, const uint64_t* offsets_in, uint64_t n_edges, uint64_t n_members,
           int mem_kind, hipStream_t st) {
   Temps tmp(st);
@@ -566,13 +605,21 @@ int build(hm_graph* H, const uint32_t* members_in, const uint64_t* offsets_in, u
     offsets = doff;
   }
   const uint64_t E = n_edges;
+  const uint64_t N = H->n_nodes;
   const uint64_t n_tiles = (E + kTile - 1) / kTile;
+  const bool keep_bits = H->n_nodes <= bitset_max_nodes();
+  const bool one_pass = keep_bits && E <= one_pass_max_edges();
+  const uint32_t R = degree_copies(N);
+  const uint64_t NR = N * R;
+
   DevFlags* flags = nullptr;
+  unsigned long long* dev_totals = nullptr;
   uint32_t *sm = nullptr, *size = nullptr, *tile_cnt = nullptr;
   unsigned long long *hash = nullptr, *slots = nullptr, *slot_of = nullptr;
   uint8_t* first = nullptr;
   const unsigned long long cap = pow2_capacity(E);
   HM_TRY(tmp.get(&flags, 1));
+  HM_TRY(tmp.get(&dev_totals, kTileN));
   HM_TRY(tmp.get(&sm, n_members));
   HM_TRY(tmp.get(&size, E));
   HM_TRY(tmp.get(&hash, E));
@@ -585,112 +632,102 @@ int build(hm_graph* H, const uint32_t* members_in, const uint64_t* offsets_in, u
   HM_TRY(rep.take());
   Report* rep_dev = nullptr;
   HM_HIP(hipHostGetDevicePointer(reinterpret_cast<void**>(&rep_dev), rep.p, 0));
-  {
-    FillRegions r{};
-    r.ptr[0] = flags;
-    r.count[0] = sizeof(DevFlags) / 8;
-    r.value[0] = 0;
-    r.wide[0] = 1;
-    r.ptr[1] = &flags->err_edge;   // no offending hyperedge yet
-    r.count[1] = 1;
-    r.value[1] = 0xFFFFFFFFu;
-    r.wide[1] = 0;
-    r.ptr[2] = slots;
-    r.count[2] = cap;
-    r.value[2] = kEmpty64;
-    r.wide[2] = 1;
-    r.n = 3;
-    k_multi_fill<<<grid_for(cap), 256, 0, st>>>(r);
-  }
+  if (!E) *rep.p = Report{};
+
+  // buffers sized by the unique counts (bounds in one pass), and their fills
+  uint32_t *deg2 = nullptr, *deg3 = nullptr, *deg4 = nullptr, *cur3 = nullptr, *cur4 = nullptr;
+  auto allocate = [&](uint64_t n2, uint64_t n3, uint64_t n4, uint64_t n_unique, uint64_t n_unique_members,
+                      FillList& fl) -> int {
+    HM_TRY(owned(&H->e2, 2 * n2));
+    HM_TRY(owned(&H->e3, 3 * n3));
+    HM_TRY(owned(&H->e4, 4 * n4));
+    HM_TRY(owned(&H->all_members, n_unique_members));
+    HM_TRY(owned(&H->all_off, n_unique + 1));
+    const unsigned long long c2 = pow2_capacity(n2), c3 = pow2_capacity(n3), c4 = pow2_capacity(n4);
+    HM_TRY(owned(&H->hs2.slot, c2));
+    HM_TRY(owned(&H->hs3.slot, 2 * c3));
+    HM_TRY(owned(&H->hs4.slot, 2 * c4));
+    H->hs2.mask = c2 - 1;
+    H->hs3.mask = c3 - 1;
+    H->hs4.mask = c4 - 1;
+    if (keep_bits) {
+      H->words = (H->n_nodes + 31) / 32;
+      HM_TRY(owned(&H->bits, N * H->words));
+    }
+    HM_TRY(tmp.get(&deg2, NR));
+    HM_TRY(tmp.get(&deg3, NR));
+    HM_TRY(tmp.get(&deg4, NR));
+    HM_TRY(tmp.get(&cur3, NR + 1));
+    HM_TRY(tmp.get(&cur4, NR + 1));
+    HM_TRY(owned(&H->g2_off, N + 1));
+    HM_TRY(owned(&H->g2_adj, 2 * n2));
+    HM_TRY(owned(&H->i3_off, N + 1));
+    HM_TRY(owned(&H->i3_idx, 3 * n3));
+    HM_TRY(owned(&H->i4_off, N + 1));
+    HM_TRY(owned(&H->i4_idx, 4 * n4));
+    HM_TRY(owned(&H->hist, uint64_t(kHistCopies) * kExactHistStride));
+    HM_TRY(owned(&H->sample_hist, uint64_t(kHistCopies) * kSampleHistStride + 8));
+    fl.add(H->hs2.slot, c2, kEmpty64, 1);
+    fl.add(H->hs3.slot, 2 * c3, kEmpty64, 1);
+    fl.add(H->hs4.slot, 2 * c4, kEmpty64, 1);
+    fl.add(H->sample_hist, uint64_t(kHistCopies) * kSampleHistStride + 8, 0, 1);
+    fl.add(H->hist, uint64_t(kHistCopies) * kExactHistStride, 0, 1);
+    fl.add(deg2, NR, 0, 0);
+    fl.add(deg3, NR, 0, 0);
+    fl.add(deg4, NR, 0, 0);
+    if (keep_bits) fl.add(H->bits, N * H->words, 0, 0);
+    fl.add(H->all_off, 1, 0, 1);   // all_off[0]; the rest is written by the gather
+    return HM_OK;
+  };
+  // validation and counting fills
+  FillList fl;
+  fl.add(flags, sizeof(DevFlags) / 8, 0, 1);
+  fl.add(&flags->err_edge, 1, 0xFFFFFFFFu, 0);   // no offending hyperedge yet
+  fl.add(slots, cap, kEmpty64, 1);
+  if (one_pass) HM_TRY(allocate(E, E, E, E, n_members, fl));
+  fl.launch(st);
   if (E) {
     // validate and sort; collapse repeated hyperedges onto first occurrences
     k_prepare<<<grid_for(E), 256, 0, st>>>(members, offsets, E, n_members, H->n_nodes, sm, size, hash, flags);
     k_dedup_insert<<<grid_for(E), 256, 0, st>>>(sm, offsets, size, hash, E, slots, cap - 1, slot_of);
     k_first_tiles<<<unsigned(n_tiles), kTile, 0, st>>>(size, E, slots, slot_of, first, tile_cnt, flags);
-    k_tile_scan<<<1, 1024, 0, st>>>(tile_cnt, n_tiles, flags, rep_dev);
+    k_tile_scan<<<1, 1024, 0, st>>>(tile_cnt, n_tiles, flags, rep_dev, dev_totals);
     HM_HIP(hipGetLastError());
-  } else {
-    *rep.p = Report{};
   }
-  HM_HIP(hipStreamSynchronize(st));
-  const DevFlags got = rep.p->flags;
-  unsigned long long tot[kTileN];
-  for (int k = 0; k < kTileN; ++k) tot[k] = rep.p->totals[k];
-  if (got.err) {
-    const char* what = (got.err & kErrOffsets) ? "offsets[0] is not 0, or offsets decrease or exceed n_members"
-                       : (got.err & kErrEmpty) ? "an empty hyperedge"
-                       : (got.err & kErrBadId) ? "a node id >= n_nodes"
-                                               : "a node repeated inside a hyperedge";
-    set_error("invalid hypergraph: %s (first offending hyperedge index %u)", what, got.err_edge);
-    return HM_EINVAL;
-  }
-  H->n_unique = tot[0];
-  H->n_by_size[2] = tot[1];
-  H->n_by_size[3] = tot[2];
-  H->n_by_size[4] = tot[3];
-  H->n_by_size[5] = tot[0] - tot[1] - tot[2] - tot[3];
-  H->n_singletons = got.singletons;
-  H->n_duplicates = got.duplicates;
-  H->n_unique_members = tot[4];
-  const uint64_t n2 = H->n_by_size[2], n3 = H->n_by_size[3], n4 = H->n_by_size[4];
-  const uint64_t N = H->n_nodes;
-  const uint32_t R = degree_copies(N);
-  const uint64_t NR = N * R;
 
-  // everything the unique hyperedges are written into
-  HM_TRY(owned(&H->e2, 2 * n2));
-  HM_TRY(owned(&H->e3, 3 * n3));
-  HM_TRY(owned(&H->e4, 4 * n4));
-  HM_TRY(owned(&H->all_members, H->n_unique_members));
-  HM_TRY(owned(&H->all_off, H->n_unique + 1));
-  const unsigned long long c2 = pow2_capacity(n2), c3 = pow2_capacity(n3), c4 = pow2_capacity(n4);
-  HM_TRY(owned(&H->hs2.slot, c2));
-  HM_TRY(owned(&H->hs3.slot, 2 * c3));
-  HM_TRY(owned(&H->hs4.slot, 2 * c4));
-  H->hs2.mask = c2 - 1;
-  H->hs3.mask = c3 - 1;
-  H->hs4.mask = c4 - 1;
-  const bool keep_bits = H->n_nodes <= bitset_max_nodes();
-  if (keep_bits) {
-    H->words = (H->n_nodes + 31) / 32;
-    HM_TRY(owned(&H->bits, N * H->words));
-  }
-  uint32_t *deg2 = nullptr, *deg3 = nullptr, *deg4 = nullptr, *cur3 = nullptr, *cur4 = nullptr;
-  HM_TRY(tmp.get(&deg2, NR));
-  HM_TRY(tmp.get(&deg3, NR));
-  HM_TRY(tmp.get(&deg4, NR));
-  HM_TRY(tmp.get(&cur3, NR + 1));
-  HM_TRY(tmp.get(&cur4, NR + 1));
-  HM_TRY(owned(&H->g2_off, N + 1));
-  HM_TRY(owned(&H->g2_adj, 2 * n2));
-  HM_TRY(owned(&H->i3_off, N + 1));
-  HM_TRY(owned(&H->i3_idx, 3 * n3));
-  HM_TRY(owned(&H->i4_off, N + 1));
-  HM_TRY(owned(&H->i4_idx, 4 * n4));
-  HM_TRY(owned(&H->hist, uint64_t(kHistCopies) * kExactHistStride));
-  HM_TRY(owned(&H->sample_hist, uint64_t(kHistCopies) * kSampleHistStride + 8));
-  {
-    FillRegions r{};
-    auto add = [&r](void* p, unsigned long long n, unsigned long long v, uint32_t wide) {
-      r.ptr[r.n] = p;
-      r.count[r.n] = n;
-      r.value[r.n] = v;
-      r.wide[r.n] = wide;
-      ++r.n;
-    };
-    add(H->hs2.slot, c2, kEmpty64, 1);
-    add(H->hs3.slot, 2 * c3, kEmpty64, 1);
-    add(H->hs4.slot, 2 * c4, kEmpty64, 1);
-    add(H->sample_hist, uint64_t(kHistCopies) * kSampleHistStride + 8, 0, 1);
-    add(H->hist, uint64_t(kHistCopies) * kExactHistStride, 0, 1);
-    add(deg2, NR, 0, 0);
-    add(deg3, NR, 0, 0);
-    add(deg4, NR, 0, 0);
-    if (keep_bits) add(H->bits, N * H->words, 0, 0);
-    if (H->n_unique == 0) add(H->all_off, 1, 0, 1);
-    unsigned long long most = 0;
-    for (uint32_t k = 0; k < r.n; ++k) most = std::max(most, r.count[k]);
-    k_multi_fill<<<grid_for(most), 256, 0, st>>>(r);
+  // what the report says: error, or the unique counts
+  auto read_report = [&]() -> int {
+    HM_HIP(hipStreamSynchronize(st));
+    const DevFlags got = rep.p->flags;
+    if (got.err) {
+      const char* what = (got.err & kErrOffsets) ? "offsets[0] is not 0, or offsets decrease or exceed n_members"
+                         : (got.err & kErrEmpty) ? "an empty hyperedge"
+                         : (got.err & kErrBadId) ? "a node id >= n_nodes"
+                                                 : "a node repeated inside a hyperedge";
+      set_error("invalid hypergraph: %s (first offending hyperedge index %u)", what, got.err_edge);
+      return HM_EINVAL;
+    }
+    const unsigned long long* tot = rep.p->totals;
+    H->n_unique = tot[0];
+    H->n_by_size[2] = tot[1];
+    H->n_by_size[3] = tot[2];
+    H->n_by_size[4] = tot[3];
+    H->n_by_size[5] = tot[0] - tot[1] - tot[2] - tot[3];
+    H->n_singletons = got.singletons;
+    H->n_duplicates = got.duplicates;
+    H->n_unique_members = tot[4];
+    return HM_OK;
+  };
+  // host-side bounds of the unique counts for grid sizes: exact after the
+  // report, E in one pass
+  uint64_t b2 = E, b34 = 2 * E;
+  if (!one_pass) {
+    HM_TRY(read_report());
+    FillList fl2;
+    HM_TRY(allocate(H->n_by_size[2], H->n_by_size[3], H->n_by_size[4], H->n_unique, H->n_unique_members, fl2));
+    fl2.launch(st);
+    b2 = H->n_by_size[2];
+    b34 = H->n_by_size[3] + H->n_by_size[4];
   }
   if (E) {
     GatherOut g;
@@ -708,8 +745,8 @@ int build(hm_graph* H, const uint32_t* members_in, const uint64_t* offsets_in, u
     g.deg3 = deg3;
     g.deg4 = deg4;
     g.R = R;
-    g.n_unique = H->n_unique;
-    g.n_members = H->n_unique_members;
+    g.totals = dev_totals;
+    g.flags = flags;
     k_gather_tiles<<<unsigned(n_tiles), kTile, 0, st>>>(sm, offsets, size, E, first, tile_cnt, g);
   }
   HM_HIP(hipGetLastError());
@@ -729,21 +766,22 @@ int build(hm_graph* H, const uint32_t* members_in, const uint64_t* offsets_in, u
                                                          uint32_t(N), R);
     HM_HIP(hipGetLastError());
   }
-  if (keep_bits && (n2 || n3 + n4)) {
+  if (keep_bits && (b2 || b34)) {
     // ascending rows straight from the bit rows, and the incidence lists
-    const uint32_t row_blocks = n2 ? grid_for(N * kWave) : 0;
-    const uint32_t inc_blocks = (n3 + n4) ? grid_for(n3 + n4) : 0;
+    const uint32_t row_blocks = b2 ? grid_for(N * kWave) : 0;
+    const uint32_t inc_blocks = b34 ? grid_for(b34) : 0;
     k_rows_and_incidence<<<row_blocks + inc_blocks, 256, 0, st>>>(H->bits, uint32_t(N), H->words, H->g2_off,
-                                                                  H->g2_adj, row_blocks, H->e3, n3, cur3, H->i3_idx,
-                                                                  H->e4, n4, cur4, H->i4_idx, R);
+                                                                  H->g2_adj, row_blocks, H->e3, cur3, H->i3_idx,
+                                                                  H->e4, cur4, H->i4_idx, R, dev_totals, flags);
     HM_HIP(hipGetLastError());
-  } else if (n3 + n4) {
-    k_inc_fill<<<grid_for(n3 + n4), 256, 0, st>>>(H->e3, n3, cur3, H->i3_idx, H->e4, n4, cur4, H->i4_idx, R);
+  } else if (b34) {
+    k_inc_fill<<<grid_for(b34), 256, 0, st>>>(H->e3, cur3, H->i3_idx, H->e4, cur4, H->i4_idx, R, dev_totals, flags);
     HM_HIP(hipGetLastError());
   }
-  if (n2 && !keep_bits) {
+  if (!keep_bits && b2) {
     // ascending rows from a radix sort of directed pairs, with the position
     // in e2 of each entry's pair
+    const uint64_t n2 = b2;
     const int B = node_bits(H->n_nodes);
     const uint64_t m = 2 * n2;
     unsigned long long *keys, *keys_tmp;
@@ -758,6 +796,7 @@ int build(hm_graph* H, const uint32_t* members_in, const uint64_t* offsets_in, u
     k_pair_adj<<<grid_for(m), 256, 0, st>>>(keys, m, (1ull << B) - 1, H->g2_adj);
     HM_HIP(hipGetLastError());
   }
+  if (one_pass) return read_report();
   // no wait: later calls on the stream are ordered after the build, and the
   // temporaries return to the cache only once it has run
   return HM_OK;

@@ -31,6 +31,11 @@ constexpr unsigned long long kEmpty64 = ~0ull;
 constexpr uint32_t kBitsetMaxNodes = 8192;
 uint32_t bitset_max_nodes();
 uint32_t sample_chunk_scale();
+// graphs with bit rows and at most this many input hyperedges are built in
+// one pass, with buffers sized by upper bounds (largest value and default of
+// HM_OPT_ONE_PASS_MAX_EDGES)
+constexpr uint64_t kOnePassMaxEdges = 1ull << 20;
+uint64_t one_pass_max_edges();
 
 // ----------------------------------------------------------------- errors
 void set_error(const char* fmt, ...);

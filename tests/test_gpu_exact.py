@@ -217,6 +217,51 @@ def test_many_graphs_created_and_destroyed_in_stream_order(hm):
         assert np.array_equal(c.cpu().numpy(), want[i % len(hs)]), i
 
 
+@pytest.fixture(params=["one_pass", "two_pass"])
+def build_mode(hm, request):
+    """Graphs built in one pass (buffers sized by bounds) or in two (sized
+    exactly after the counting pass)."""
+    hm.hm_set_option(hm.HM_OPT_ONE_PASS_MAX_EDGES, (1 << 20) if request.param == "one_pass" else 0)
+    yield request.param
+    hm.hm_set_option(hm.HM_OPT_ONE_PASS_MAX_EDGES, 1 << 20)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_build_modes_match_oracle(hm, build_mode, seed):
+    h = W.random_small(500 + seed, 20 + 9 * seed, 100 + 90 * seed, {1: 0.05, 2: 0.5, 3: 0.3, 4: 0.1, 5: 0.05},
+                       allow_dups=True)
+    nh = core.normalise(h)
+    with hm.hm_graph_create(h.members, h.offsets, h.n_nodes) as g:
+        st = g.stats()
+        assert (st["n2"], st["n3"], st["n4"]) == (nh.count(2), nh.count(3), nh.count(4))
+        for j in (2, 3, 4):
+            assert np.array_equal(g.export(j).astype(np.int64), nh.edges(j))
+        for k in (3, 4):
+            assert np.array_equal(hm.count_exact(g, k).cpu().numpy(), core.count_exact(h, k)), k
+        est, _ = hm.count_sampled(g, 4, 0.5, 3)
+        assert np.isfinite(est.cpu().numpy()).all()
+
+
+@pytest.mark.parametrize("edges,n", [([[0, 1], [2, 2]], 3), ([[0, 7]], 3), ([[0, 1], [1, 2, 9]], 4)])
+def test_build_modes_reject_invalid_input(hm, build_mode, edges, n):
+    h = W.from_lists(edges, n)
+    with pytest.raises(hm.HMError) as e:
+        hm.hm_graph_create(h.members, h.offsets, n)
+    assert e.value.code == -1
+    # the library is still usable afterwards
+    ok = W.random_small(7, 12, 40, {2: 0.6, 3: 0.4})
+    with hm.hm_graph_create(ok.members, ok.offsets, ok.n_nodes) as g:
+        assert np.array_equal(hm.count_exact(g, 4).cpu().numpy(), core.count_exact(ok, 4))
+
+
+def test_one_pass_option_bounds(hm):
+    with pytest.raises(hm.HMError):
+        hm.hm_set_option(hm.HM_OPT_ONE_PASS_MAX_EDGES, (1 << 20) + 1)
+    with pytest.raises(hm.HMError):
+        hm.hm_set_option(hm.HM_OPT_ONE_PASS_MAX_EDGES, -1)
+    assert hm.hm_get_option(hm.HM_OPT_ONE_PASS_MAX_EDGES) == 1 << 20
+
+
 def test_wide_bit_rows(hm):
     """More than 64 words per bit row (N > 2048): the word loop of the pairs-only kernel."""
     base = W.random_small(3000, 80, 900, {2: 0.6, 3: 0.3, 4: 0.1})
