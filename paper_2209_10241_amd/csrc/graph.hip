@@ -536,6 +536,8 @@ std::vector<Report*> g_report_pool;
 
 struct PinnedReport {
   Report* p = nullptr;
+  hipStream_t st = nullptr;
+  bool pending = false;   // a kernel enqueued on st may still write to it
   int take() {
     {
       std::lock_guard<std::mutex> lock(g_report_mu);
@@ -556,6 +558,7 @@ struct PinnedReport {
   }
   ~PinnedReport() {
     if (!p) return;
+    if (pending) (void)hipStreamSynchronize(st);
     std::lock_guard<std::mutex> lock(g_report_mu);
     g_report_pool.push_back(p);
   }
@@ -692,12 +695,15 @@ int build(hm_graph* H, const uint32_t* members_in, const uint64_t* offsets_in, u
     k_dedup_insert<<<grid_for(E), 256, 0, st>>>(sm, offsets, size, hash, E, slots, cap - 1, slot_of);
     k_first_tiles<<<unsigned(n_tiles), kTile, 0, st>>>(size, E, slots, slot_of, first, tile_cnt, flags);
     k_tile_scan<<<1, 1024, 0, st>>>(tile_cnt, n_tiles, flags, rep_dev, dev_totals);
+    rep.st = st;
+    rep.pending = true;
     HM_HIP(hipGetLastError());
   }
 
   // what the report says: error, or the unique counts
   auto read_report = [&]() -> int {
     HM_HIP(hipStreamSynchronize(st));
+    rep.pending = false;
     const DevFlags got = rep.p->flags;
     if (got.err) {
       const char* what = (got.err & kErrOffsets) ? "offsets[0] is not 0, or offsets decrease or exceed n_members"
