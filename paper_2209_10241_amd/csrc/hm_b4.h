@@ -185,13 +185,19 @@ __device__ void b4_edge_bits_count(uint32_t a, uint32_t b, uint32_t c, const uin
       count_class(lut, h_main, h_sub, pt, kPairBits4);
     }
   }
-  uint32_t n[8];
-  n[1] = n1; n[2] = n2; n[3] = n3; n[4] = n4; n[5] = n5; n[6] = n6; n[7] = n7;
+  // Reduce over the lanes that hold words (the first min(W, 64)); a
+  // combination's total over the wavefront is below the node count, at most
+  // 8192, so two of them share a 32-bit word.
+  uint32_t pk[4] = {n1 | (n2 << 16), n3 | (n4 << 16), n5 | (n6 << 16), n7};
+  uint32_t width = 1;
+  while (width < W && width < uint32_t(kWave)) width <<= 1;
+  for (uint32_t o = width >> 1; o > 0; o >>= 1) {
 #pragma unroll
-  for (int k = 1; k < 8; ++k) {
-#pragma unroll
-    for (int o = kWave / 2; o > 0; o >>= 1) n[k] += __shfl_xor(n[k], o, kWave);
+    for (int k = 0; k < 4; ++k) pk[k] += __shfl_xor(pk[k], int(o), kWave);
   }
+  uint32_t n[8];
+  n[1] = pk[0] & 0xFFFFu; n[2] = pk[0] >> 16; n[3] = pk[1] & 0xFFFFu; n[4] = pk[1] >> 16;
+  n[5] = pk[2] & 0xFFFFu; n[6] = pk[2] >> 16; n[7] = pk[3];
   if (lane == 0) {
 #pragma unroll
     for (uint32_t cmb = 1; cmb < 8; ++cmb) {
