@@ -39,13 +39,38 @@ __device__ inline unsigned long long tuple_hash(const uint32_t* m, uint32_t s) {
   return h;
 }
 
+// Up to sixteen fills in one launch.
+struct FillRegions {
+  void* ptr[16];
+  unsigned long long count[16];
+  unsigned long long value[16];
+  uint32_t wide[16];   // 1: 64-bit elements, 0: 32-bit
+  uint32_t n;
+};
+
+__device__ void multi_fill(const FillRegions& r) {
+  const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
+  for (uint32_t k = 0; k < r.n; ++k) {
+    for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < r.count[k]; i += stride) {
+      if (r.wide[k]) static_cast<unsigned long long*>(r.ptr[k])[i] = r.value[k];
+      else static_cast<uint32_t*>(r.ptr[k])[i] = uint32_t(r.value[k]);
+    }
+  }
+}
+
+__global__ void k_multi_fill(FillRegions r) { multi_fill(r); }
+
 // One thread per input hyperedge: copy its members, sort them, check ids and
 // repeats, record its size and hash.  Offsets start at 0, never decrease and
 // stay within the n_members entries of members.
+//
+// Each hyperedge's error code (kErr* bits, 0 when valid) goes to ecode; the
+// workgroups also carry out `fills` (the tables the later kernels start from).
 __global__ void k_prepare(const uint32_t* __restrict__ members, const uint64_t* __restrict__ offsets,
                           uint64_t n_edges, uint64_t n_members, uint32_t n_nodes, uint32_t* __restrict__ sm,
                           uint32_t* __restrict__ size, unsigned long long* __restrict__ hash,
-                          DevFlags* flags) {
+                          uint8_t* __restrict__ ecode, FillRegions fills) {
+  multi_fill(fills);
   for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n_edges;
        i += uint64_t(gridDim.x) * blockDim.x) {
     const uint64_t b = offsets[i], e = offsets[i + 1];
@@ -89,10 +114,7 @@ __global__ void k_prepare(const uint32_t* __restrict__ members, const uint64_t* 
       size[i] = s;
       hash[i] = tuple_hash(out, s);
     }
-    if (err) {
-      atomicOr(&flags->err, err);
-      atomicMin(&flags->err_edge, uint32_t(i < 0xFFFFFFFFull ? i : 0xFFFFFFFEull));
-    }
+    ecode[i] = uint8_t(err);
   }
 }
 
@@ -141,6 +163,13 @@ __global__ void k_dedup_insert(const uint32_t* __restrict__ sm, const uint64_t* 
 // writes it out.
 constexpr uint32_t kTile = 256;
 constexpr int kTileN = 5;   // unique, unique of size 2, 3, 4, members of the unique
+// per tile: the kTileN counters above, then singletons, repeats (collapsed
+// duplicates), the OR of the error codes and the first erroneous index
+constexpr int kTileS = kTileN + 4;
+enum : int { kTSingles = kTileN, kTDups = kTileN + 1, kTErr = kTileN + 2, kTErrMin = kTileN + 3 };
+// up to this many tiles, a one-pass build lets every workgroup of the gather
+// sum the counts of the tiles before it instead of running k_tile_scan
+constexpr uint64_t kSelfOffsetTiles = 1024;
 
 // Per-thread contribution of hyperedge i to the five tile counters.
 __device__ inline void tile_terms(uint32_t first, uint32_t s, uint32_t t[kTileN]) {
@@ -154,14 +183,16 @@ __device__ inline void tile_terms(uint32_t first, uint32_t s, uint32_t t[kTileN]
 __global__ void __launch_bounds__(kTile) k_first_tiles(const uint32_t* __restrict__ size, uint64_t n_edges,
                                                         const unsigned long long* __restrict__ slots,
                                                         const unsigned long long* __restrict__ slot_of,
+                                                        const uint8_t* __restrict__ ecode,
                                                         uint8_t* __restrict__ first_out,
-                                                        uint32_t* __restrict__ tile_cnt, DevFlags* flags) {
-  __shared__ uint32_t part[kTileN][kTile / kWave];
+                                                        uint32_t* __restrict__ tile_cnt) {
+  __shared__ uint32_t part[kTileS][kTile / kWave];
   const uint64_t i = uint64_t(blockIdx.x) * kTile + threadIdx.x;
-  uint32_t first = 0, s = 0;
-  unsigned long long singles = 0, dups = 0;
+  uint32_t first = 0, s = 0, singles = 0, dups = 0, err = 0, err_at = 0xFFFFFFFFu;
   if (i < n_edges) {
     s = size[i];
+    err = ecode[i];
+    if (err) err_at = uint32_t(i);
     if (s >= 2) {
       first = uint32_t(slots[slot_of[i]]) == uint32_t(i);
       dups = !first;
@@ -173,23 +204,71 @@ __global__ void __launch_bounds__(kTile) k_first_tiles(const uint32_t* __restric
   uint32_t t[kTileN];
   tile_terms(first, s, t);
   const int wv = threadIdx.x / kWave;
+  const uint32_t lane = threadIdx.x & (kWave - 1);
   for (int k = 0; k < kTileN; ++k) {
     uint32_t w;
     (void)wave_exclusive_scan(t[k], &w);
-    if ((threadIdx.x & (kWave - 1)) == 0) part[k][wv] = w;
+    if (lane == 0) part[k][wv] = w;
   }
-  singles = wave_sum(singles);
-  dups = wave_sum(dups);
-  if ((threadIdx.x & (kWave - 1)) == 0) {
-    if (singles) atomicAdd(&flags->singletons, singles);
-    if (dups) atomicAdd(&flags->duplicates, dups);
+  singles = wave_sum_u32(singles);
+  dups = wave_sum_u32(dups);
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) {
+    err |= __shfl_xor(err, o, kWave);
+    err_at = min(err_at, uint32_t(__shfl_xor(err_at, o, kWave)));
+  }
+  if (lane == 0) {
+    part[kTSingles][wv] = singles;
+    part[kTDups][wv] = dups;
+    part[kTErr][wv] = err;
+    part[kTErrMin][wv] = err_at;
   }
   __syncthreads();
-  if (threadIdx.x < kTileN) {
-    uint32_t sum = 0;
-    for (int q = 0; q < int(kTile / kWave); ++q) sum += part[threadIdx.x][q];
-    tile_cnt[uint64_t(blockIdx.x) * kTileN + threadIdx.x] = sum;
+  if (threadIdx.x < kTileS) {
+    uint32_t x = threadIdx.x == kTErrMin ? 0xFFFFFFFFu : 0u;
+    for (int q = 0; q < int(kTile / kWave); ++q) {
+      const uint32_t y = part[threadIdx.x][q];
+      x = threadIdx.x == kTErr ? (x | y) : (threadIdx.x == kTErrMin ? min(x, y) : x + y);
+    }
+    tile_cnt[uint64_t(blockIdx.x) * kTileS + threadIdx.x] = x;
   }
+}
+
+// The validation summary of the tiles a workgroup's threads take (thread:
+// t_first, t_first + t_step, ... below t_end), reduced over the workgroup:
+// singletons, repeats, error bits, first erroneous index.  Every thread must
+// call it and receives the result.
+__device__ DevFlags tile_flags(const uint32_t* __restrict__ tile_cnt, uint64_t t_first, uint64_t t_end,
+                               uint64_t t_step) {
+  __shared__ unsigned long long s_single, s_dup;
+  __shared__ uint32_t s_err, s_min;
+  if (threadIdx.x == 0) {
+    s_single = 0;
+    s_dup = 0;
+    s_err = 0;
+    s_min = 0xFFFFFFFFu;
+  }
+  __syncthreads();
+  unsigned long long sg = 0, dp = 0;
+  uint32_t er = 0, mn = 0xFFFFFFFFu;
+  for (uint64_t t = t_first; t < t_end; t += t_step) {
+    const uint32_t* c = tile_cnt + t * kTileS;
+    sg += c[kTSingles];
+    dp += c[kTDups];
+    er |= c[kTErr];
+    mn = min(mn, c[kTErrMin]);
+  }
+  if (sg) atomicAdd(&s_single, sg);
+  if (dp) atomicAdd(&s_dup, dp);
+  if (er) atomicOr(&s_err, er);
+  if (mn != 0xFFFFFFFFu) atomicMin(&s_min, mn);
+  __syncthreads();
+  DevFlags f;
+  f.err = s_err;
+  f.err_edge = s_min;
+  f.singletons = s_single;
+  f.duplicates = s_dup;
+  return f;
 }
 
 // What the build reads back once: validation flags and the five totals.
@@ -198,25 +277,26 @@ struct Report {
   unsigned long long totals[kTileN];
 };
 
-// Exclusive scan of the tile counters in place; the five totals and the
-// validation flags go to the report (pinned host memory), the totals also to
-// dev_totals for the kernels that follow.  One workgroup of
-// 1024: thread t takes a run of consecutive tiles, the runs' sums are scanned
-// across the workgroup, and each thread then writes the offsets of its run.
-// Every count is below 2^32 (so are the incidences).
-__global__ void __launch_bounds__(1024) k_tile_scan(uint32_t* __restrict__ tile_cnt, uint64_t n_tiles,
-                                                    const DevFlags* __restrict__ flags, Report* out,
+// Exclusive scan of the tiles' position counters in place; the five totals
+// and the validation summary go to the report (pinned host memory), the
+// totals and the error bits also to dev_totals (kTileN + 1 words) for the
+// kernels that follow.  One workgroup of 1024: thread t takes a run of
+// consecutive tiles, the runs' sums are scanned across the workgroup, and each
+// thread then writes the offsets of its run.  Every count is below 2^32 (so
+// are the incidences).
+__global__ void __launch_bounds__(1024) k_tile_scan(uint32_t* __restrict__ tile_cnt, uint64_t n_tiles, Report* out,
                                                     unsigned long long* __restrict__ dev_totals) {
   __shared__ uint32_t wsum[kTileN][1024 / kWave];
   const uint32_t lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
   const uint64_t per = (n_tiles + 1023) / 1024;
   const uint64_t t0 = min(n_tiles, uint64_t(threadIdx.x) * per), t1 = min(n_tiles, t0 + per);
+  const DevFlags f = tile_flags(tile_cnt, t0, t1, 1);
   uint32_t pre[kTileN];
 #pragma unroll
   for (int k = 0; k < kTileN; ++k) pre[k] = 0;
   for (uint64_t t = t0; t < t1; ++t) {
 #pragma unroll
-    for (int k = 0; k < kTileN; ++k) pre[k] += tile_cnt[t * kTileN + k];
+    for (int k = 0; k < kTileN; ++k) pre[k] += tile_cnt[t * kTileS + k];
   }
 #pragma unroll
   for (int k = 0; k < kTileN; ++k) {
@@ -231,8 +311,8 @@ __global__ void __launch_bounds__(1024) k_tile_scan(uint32_t* __restrict__ tile_
   for (uint64_t t = t0; t < t1; ++t) {
 #pragma unroll
     for (int k = 0; k < kTileN; ++k) {
-      const uint32_t x = tile_cnt[t * kTileN + k];
-      tile_cnt[t * kTileN + k] = pre[k];
+      const uint32_t x = tile_cnt[t * kTileS + k];
+      tile_cnt[t * kTileS + k] = pre[k];
       pre[k] += x;
     }
   }
@@ -243,7 +323,10 @@ __global__ void __launch_bounds__(1024) k_tile_scan(uint32_t* __restrict__ tile_
       dev_totals[k] = pre[k];
     }
   }
-  if (threadIdx.x == 0) out->flags = *flags;
+  if (threadIdx.x == 0) {
+    out->flags = f;
+    dev_totals[kTileN] = f.err;
+  }
 }
 
 // Write the unique hyperedges out, in first-occurrence order, with everything
@@ -263,8 +346,13 @@ struct GatherOut {
   // that no counter takes more than about 1/R of its node's incidences
   uint32_t *deg2, *deg3, *deg4;
   uint32_t R;
-  const unsigned long long* totals;   // the five totals of k_tile_scan
-  const DevFlags* flags;              // nothing is written when the input is invalid
+  // self_offsets: tile_cnt holds the raw tile counters (no k_tile_scan ran);
+  // each workgroup sums those of the tiles before it, and workgroup 0 also
+  // writes the report and dev_totals.  Otherwise dev_totals holds what
+  // k_tile_scan wrote.  Nothing is written when the input is invalid.
+  bool self_offsets;
+  Report* report;
+  unsigned long long* dev_totals;
 };
 
 __global__ void __launch_bounds__(kTile) k_gather_tiles(const uint32_t* __restrict__ sm,
@@ -274,7 +362,65 @@ __global__ void __launch_bounds__(kTile) k_gather_tiles(const uint32_t* __restri
                                                          const uint32_t* __restrict__ tile_off,
                                                          GatherOut g) {
   __shared__ uint32_t part[kTileN][kTile / kWave];
-  if (g.flags->err) return;
+  __shared__ uint32_t red[2 * kTileN][kTile / kWave];
+  __shared__ uint32_t base[kTileN];
+  __shared__ unsigned long long total[kTileN];
+  const int wv = threadIdx.x / kWave;
+  const uint32_t lane = threadIdx.x & (kWave - 1);
+  __shared__ uint32_t bad;
+  if (g.self_offsets) {
+    const uint64_t n_tiles = (n_edges + kTile - 1) / kTile;
+    const DevFlags f = tile_flags(tile_off, threadIdx.x, n_tiles, kTile);
+    uint32_t before[kTileN], all[kTileN];
+#pragma unroll
+    for (int k = 0; k < kTileN; ++k) before[k] = all[k] = 0;
+    for (uint64_t t = threadIdx.x; t < n_tiles; t += kTile) {
+#pragma unroll
+      for (int k = 0; k < kTileN; ++k) {
+        const uint32_t x = tile_off[t * kTileS + k];
+        all[k] += x;
+        if (t < blockIdx.x) before[k] += x;
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < kTileN; ++k) {
+      const uint32_t b = wave_sum_u32(before[k]), a = wave_sum_u32(all[k]);
+      if (lane == 0) {
+        red[k][wv] = b;
+        red[kTileN + k][wv] = a;
+      }
+    }
+    __syncthreads();
+    if (threadIdx.x < 2 * kTileN) {
+      uint32_t x = 0;
+      for (int q = 0; q < kTile / kWave; ++q) x += red[threadIdx.x][q];
+      if (threadIdx.x < kTileN) {
+        base[threadIdx.x] = x;
+      } else {
+        total[threadIdx.x - kTileN] = x;
+        if (blockIdx.x == 0) {
+          g.report->totals[threadIdx.x - kTileN] = x;
+          g.dev_totals[threadIdx.x - kTileN] = x;
+        }
+      }
+    }
+    if (threadIdx.x == 0) {
+      bad = f.err;
+      if (blockIdx.x == 0) {
+        g.report->flags = f;
+        g.dev_totals[kTileN] = f.err;
+      }
+    }
+    __syncthreads();
+  } else {
+    if (threadIdx.x < kTileN) {
+      base[threadIdx.x] = tile_off[uint64_t(blockIdx.x) * kTileS + threadIdx.x];
+      total[threadIdx.x] = g.dev_totals[threadIdx.x];
+    }
+    if (threadIdx.x == 0) bad = uint32_t(g.dev_totals[kTileN]);
+    __syncthreads();
+  }
+  if (bad) return;
   const uint64_t i = uint64_t(blockIdx.x) * kTile + threadIdx.x;
   uint32_t first = 0, s = 0;
   if (i < n_edges) {
@@ -284,25 +430,23 @@ __global__ void __launch_bounds__(kTile) k_gather_tiles(const uint32_t* __restri
   uint32_t t[kTileN];
   tile_terms(first, s, t);
   uint32_t pre[kTileN];
-  const int wv = threadIdx.x / kWave;
   for (int k = 0; k < kTileN; ++k) {
     uint32_t tot;
     pre[k] = wave_exclusive_scan(t[k], &tot);
-    if ((threadIdx.x & (kWave - 1)) == 0) part[k][wv] = tot;
+    if (lane == 0) part[k][wv] = tot;
   }
   __syncthreads();
   if (!first) return;
   unsigned long long pos[kTileN];
   for (int k = 0; k < kTileN; ++k) {
-    unsigned long long p = tile_off[uint64_t(blockIdx.x) * kTileN + k] + pre[k];
+    unsigned long long p = base[k] + pre[k];
     for (int q = 0; q < wv; ++q) p += part[k][q];
     pos[k] = p;
   }
   const uint32_t* m = sm + off[i];
   for (uint32_t j = 0; j < s; ++j) g.all_members[pos[4] + j] = m[j];
   g.all_off[pos[0]] = pos[4];
-  const unsigned long long n_unique = g.totals[0];
-  if (pos[0] + 1 == n_unique) g.all_off[n_unique] = g.totals[4];
+  if (pos[0] + 1 == total[0]) g.all_off[total[0]] = total[4];
   if (s == 2) {
     const uint32_t a = m[0], b = m[1];
     g.e2[2 * pos[1]] = a;
@@ -328,25 +472,6 @@ __global__ void __launch_bounds__(kTile) k_gather_tiles(const uint32_t* __restri
     uint32_t* deg = s == 3 ? g.deg3 : g.deg4;
     const uint32_t cp = uint32_t(s == 3 ? pos[2] : pos[3]) & (g.R - 1);
     for (uint32_t j = 0; j < s; ++j) atomicAdd(&deg[uint64_t(m[j]) * g.R + cp], 1u);
-  }
-}
-
-// Up to sixteen fills in one launch.
-struct FillRegions {
-  void* ptr[16];
-  unsigned long long count[16];
-  unsigned long long value[16];
-  uint32_t wide[16];   // 1: 64-bit elements, 0: 32-bit
-  uint32_t n;
-};
-
-__global__ void k_multi_fill(FillRegions r) {
-  const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
-  for (uint32_t k = 0; k < r.n; ++k) {
-    for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < r.count[k]; i += stride) {
-      if (r.wide[k]) static_cast<unsigned long long*>(r.ptr[k])[i] = r.value[k];
-      else static_cast<uint32_t*>(r.ptr[k])[i] = uint32_t(r.value[k]);
-    }
   }
 }
 
@@ -440,12 +565,12 @@ __device__ void inc_fill(const uint32_t* __restrict__ e3, uint64_t n3, uint32_t*
   }
 }
 
-// (the counts of 3- and 4-node hyperedges are totals[2] and totals[3] of
-// k_tile_scan; nothing is written when the input is invalid)
+// (the counts of 3- and 4-node hyperedges are totals[2] and totals[3];
+// nothing is written when the input is invalid, totals[kTileN] != 0)
 __global__ void k_inc_fill(const uint32_t* __restrict__ e3, uint32_t* cur3, uint32_t* idx3,
                            const uint32_t* __restrict__ e4, uint32_t* cur4, uint32_t* idx4, uint32_t R,
-                           const unsigned long long* __restrict__ totals, const DevFlags* __restrict__ flags) {
-  if (flags->err) return;
+                           const unsigned long long* __restrict__ totals) {
+  if (totals[kTileN]) return;
   inc_fill(e3, totals[2], cur3, idx3, e4, totals[3], cur4, idx4, R, blockIdx.x, gridDim.x);
 }
 
@@ -455,9 +580,8 @@ __global__ void k_rows_and_incidence(const uint32_t* __restrict__ bits, uint32_t
                                      const uint32_t* __restrict__ row_off, uint32_t* __restrict__ adj,
                                      uint32_t row_blocks, const uint32_t* __restrict__ e3, uint32_t* cur3,
                                      uint32_t* idx3, const uint32_t* __restrict__ e4, uint32_t* cur4, uint32_t* idx4,
-                                     uint32_t R, const unsigned long long* __restrict__ totals,
-                                     const DevFlags* __restrict__ flags) {
-  if (flags->err) return;
+                                     uint32_t R, const unsigned long long* __restrict__ totals) {
+  if (totals[kTileN]) return;
   if (blockIdx.x < row_blocks)
     rows_from_bits(bits, n, W, row_off, adj, blockIdx.x, row_blocks);
   else
@@ -612,25 +736,24 @@ int build(hm_graph* H, const uint32_t* members_in, const uint64_t* offsets_in, u
   const uint64_t n_tiles = (E + kTile - 1) / kTile;
   const bool keep_bits = H->n_nodes <= bitset_max_nodes();
   const bool one_pass = keep_bits && E <= one_pass_max_edges();
+  const bool self_offsets = one_pass && n_tiles <= kSelfOffsetTiles;
   const uint32_t R = degree_copies(N);
   const uint64_t NR = N * R;
 
-  DevFlags* flags = nullptr;
   unsigned long long* dev_totals = nullptr;
   uint32_t *sm = nullptr, *size = nullptr, *tile_cnt = nullptr;
   unsigned long long *hash = nullptr, *slots = nullptr, *slot_of = nullptr;
-  uint8_t* first = nullptr;
+  uint8_t *first = nullptr, *ecode = nullptr;
   const unsigned long long cap = pow2_capacity(E);
-  HM_TRY(tmp.get(&flags, 1));
-  HM_TRY(tmp.get(&dev_totals, kTileN));
+  HM_TRY(tmp.get(&dev_totals, kTileN + 1));
   HM_TRY(tmp.get(&sm, n_members));
   HM_TRY(tmp.get(&size, E));
   HM_TRY(tmp.get(&hash, E));
   HM_TRY(tmp.get(&slots, cap));
   HM_TRY(tmp.get(&slot_of, E));
   HM_TRY(tmp.get(&first, E));
-  HM_TRY(tmp.get(&tile_cnt, n_tiles * kTileN));
-  static_assert(sizeof(DevFlags) % 8 == 0, "flags are cleared as 64-bit words");
+  HM_TRY(tmp.get(&ecode, E));
+  HM_TRY(tmp.get(&tile_cnt, n_tiles * kTileS));
   PinnedReport rep;
   HM_TRY(rep.take());
   Report* rep_dev = nullptr;
@@ -682,19 +805,21 @@ int build(hm_graph* H, const uint32_t* members_in, const uint64_t* offsets_in, u
     fl.add(H->all_off, 1, 0, 1);   // all_off[0]; the rest is written by the gather
     return HM_OK;
   };
-  // validation and counting fills
+  // the dedup table (and in one pass every output table), filled by k_prepare
   FillList fl;
-  fl.add(flags, sizeof(DevFlags) / 8, 0, 1);
-  fl.add(&flags->err_edge, 1, 0xFFFFFFFFu, 0);   // no offending hyperedge yet
   fl.add(slots, cap, kEmpty64, 1);
   if (one_pass) HM_TRY(allocate(E, E, E, E, n_members, fl));
-  fl.launch(st);
+  if (!E) fl.launch(st);
   if (E) {
     // validate and sort; collapse repeated hyperedges onto first occurrences
-    k_prepare<<<grid_for(E), 256, 0, st>>>(members, offsets, E, n_members, H->n_nodes, sm, size, hash, flags);
+    unsigned long long most = E;
+    for (uint32_t k = 0; k < fl.r.n; ++k) most = std::max(most, fl.r.count[k]);
+    k_prepare<<<grid_for(most), 256, 0, st>>>(members, offsets, E, n_members, H->n_nodes, sm, size, hash, ecode,
+                                              fl.r);
     k_dedup_insert<<<grid_for(E), 256, 0, st>>>(sm, offsets, size, hash, E, slots, cap - 1, slot_of);
-    k_first_tiles<<<unsigned(n_tiles), kTile, 0, st>>>(size, E, slots, slot_of, first, tile_cnt, flags);
-    k_tile_scan<<<1, 1024, 0, st>>>(tile_cnt, n_tiles, flags, rep_dev, dev_totals);
+    k_first_tiles<<<unsigned(n_tiles), kTile, 0, st>>>(size, E, slots, slot_of, ecode, first, tile_cnt);
+    // in one pass with few tiles the gather sums the tile counts itself
+    if (!self_offsets) k_tile_scan<<<1, 1024, 0, st>>>(tile_cnt, n_tiles, rep_dev, dev_totals);
     rep.st = st;
     rep.pending = true;
     HM_HIP(hipGetLastError());
@@ -751,8 +876,9 @@ int build(hm_graph* H, const uint32_t* members_in, const uint64_t* offsets_in, u
     g.deg3 = deg3;
     g.deg4 = deg4;
     g.R = R;
-    g.totals = dev_totals;
-    g.flags = flags;
+    g.self_offsets = self_offsets;
+    g.report = rep_dev;
+    g.dev_totals = dev_totals;
     k_gather_tiles<<<unsigned(n_tiles), kTile, 0, st>>>(sm, offsets, size, E, first, tile_cnt, g);
   }
   HM_HIP(hipGetLastError());
@@ -778,10 +904,10 @@ int build(hm_graph* H, const uint32_t* members_in, const uint64_t* offsets_in, u
     const uint32_t inc_blocks = b34 ? grid_for(b34) : 0;
     k_rows_and_incidence<<<row_blocks + inc_blocks, 256, 0, st>>>(H->bits, uint32_t(N), H->words, H->g2_off,
                                                                   H->g2_adj, row_blocks, H->e3, cur3, H->i3_idx,
-                                                                  H->e4, cur4, H->i4_idx, R, dev_totals, flags);
+                                                                  H->e4, cur4, H->i4_idx, R, dev_totals);
     HM_HIP(hipGetLastError());
   } else if (b34) {
-    k_inc_fill<<<grid_for(b34), 256, 0, st>>>(H->e3, cur3, H->i3_idx, H->e4, cur4, H->i4_idx, R, dev_totals, flags);
+    k_inc_fill<<<grid_for(b34), 256, 0, st>>>(H->e3, cur3, H->i3_idx, H->e4, cur4, H->i4_idx, R, dev_totals);
     HM_HIP(hipGetLastError());
   }
   if (!keep_bits && b2) {
