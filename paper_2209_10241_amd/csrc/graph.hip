@@ -744,7 +744,9 @@ int build(hm_graph* H, const uint32_t* members_in, const uint64_t* offsets_in, u
   uint32_t *sm = nullptr, *size = nullptr, *tile_cnt = nullptr;
   unsigned long long *hash = nullptr, *slots = nullptr, *slot_of = nullptr;
   uint8_t *first = nullptr, *ecode = nullptr;
-  const unsigned long long cap = pow2_capacity(E);
+  // dedup table: a lower load (1/8 instead of 1/2) shortens the longest probe
+  // chain, which sets the dedup kernel's time; kept at 1/2 for large inputs
+  const unsigned long long cap = pow2_capacity(E <= (1ull << 20) ? 4 * E : E);
   HM_TRY(tmp.get(&dev_totals, kTileN + 1));
   HM_TRY(tmp.get(&sm, n_members));
   HM_TRY(tmp.get(&size, E));
