@@ -275,7 +275,18 @@ __device__ DevFlags tile_flags(const uint32_t* __restrict__ tile_cnt, uint64_t t
 struct Report {
   DevFlags flags;
   unsigned long long totals[kTileN];
+  uint32_t ready;   // set to 1 (after the fields above) by the kernel that writes them
+  uint32_t pad;
 };
+
+// Publish a report written by this workgroup: every thread of the workgroup
+// calls this (wrote: it wrote part of the report), and thread 0 sets `ready`
+// once those writes are visible to the host.
+__device__ inline void publish_report(Report* out, bool wrote) {
+  if (wrote) __threadfence_system();
+  __syncthreads();
+  if (threadIdx.x == 0) __hip_atomic_store(&out->ready, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
 
 // Exclusive scan of the tiles' position counters in place; the five totals
 // and the validation summary go to the report (pinned host memory), the
@@ -327,6 +338,7 @@ __global__ void __launch_bounds__(1024) k_tile_scan(uint32_t* __restrict__ tile_
     out->flags = f;
     dev_totals[kTileN] = f.err;
   }
+  publish_report(out, threadIdx.x == 0 || threadIdx.x == 1023);
 }
 
 // Write the unique hyperedges out, in first-occurrence order, with everything
@@ -411,6 +423,8 @@ __global__ void __launch_bounds__(kTile) k_gather_tiles(const uint32_t* __restri
         g.dev_totals[kTileN] = f.err;
       }
     }
+    if (blockIdx.x == 0)
+      publish_report(g.report, threadIdx.x == 0 || (threadIdx.x >= kTileN && threadIdx.x < 2 * kTileN));
     __syncthreads();
   } else {
     if (threadIdx.x < kTileN) {
@@ -672,7 +686,8 @@ struct PinnedReport {
       }
     }
     void* q = nullptr;
-    if (hipHostMalloc(&q, sizeof(Report), hipHostMallocDefault) != hipSuccess) {
+    // fine-grained: the host reads it while the kernels that write it run
+    if (hipHostMalloc(&q, sizeof(Report), hipHostMallocCoherent) != hipSuccess) {
       (void)hipGetLastError();
       set_error("pinned host allocation failed");
       return HM_ENOMEM;
@@ -687,6 +702,28 @@ struct PinnedReport {
     g_report_pool.push_back(p);
   }
 };
+
+// Wait until a kernel on `st` sets *ready (a word of fine-grained host
+// memory).  The stream is queried now and then, so that the wait ends with an
+// error when it fails or drains without setting the word.
+int wait_ready(const uint32_t* ready, hipStream_t st) {
+  for (uint64_t spin = 0;; ++spin) {
+    if (__atomic_load_n(ready, __ATOMIC_ACQUIRE)) return HM_OK;
+    if ((spin & 1023) == 1023) {
+      const hipError_t e = hipStreamQuery(st);
+      if (e == hipSuccess) {
+        if (__atomic_load_n(ready, __ATOMIC_ACQUIRE)) return HM_OK;
+        set_error("the build's report was not written");
+        return HM_EINTERNAL;
+      }
+      if (e != hipErrorNotReady) {
+        (void)hipGetLastError();
+        set_error("HIP error while building the graph: %s", hipGetErrorString(e));
+        return HM_EDEVICE;
+      }
+    }
+  }
+}
 
 // Fills gathered into one launch.
 struct FillList {
@@ -760,7 +797,12 @@ int build(hm_graph* H, const uint32_t* members_in, const uint64_t* offsets_in, u
   HM_TRY(rep.take());
   Report* rep_dev = nullptr;
   HM_HIP(hipHostGetDevicePointer(reinterpret_cast<void**>(&rep_dev), rep.p, 0));
-  if (!E) *rep.p = Report{};
+  if (!E) {
+    *rep.p = Report{};
+    rep.p->ready = 1;
+  } else {
+    __atomic_store_n(&rep.p->ready, 0u, __ATOMIC_RELEASE);
+  }
 
   // buffers sized by the unique counts (bounds in one pass), and their fills
   uint32_t *deg2 = nullptr, *deg3 = nullptr, *deg4 = nullptr, *cur3 = nullptr, *cur4 = nullptr;
@@ -829,7 +871,7 @@ int build(hm_graph* H, const uint32_t* members_in, const uint64_t* offsets_in, u
 
   // what the report says: error, or the unique counts
   auto read_report = [&]() -> int {
-    HM_HIP(hipStreamSynchronize(st));
+    HM_TRY(wait_ready(&rep.p->ready, st));
     rep.pending = false;
     const DevFlags got = rep.p->flags;
     if (got.err) {
