@@ -686,11 +686,20 @@ __device__ void sample_j2_k4_bits(const View& v, const Draws& d, uint32_t part, 
       atomicOr(&L.XS[w >> 5], 1u << (w & 31));
     }
     const uint32_t u0 = v.i3_off[u], u1 = v.i3_off[u + 1];
+    // the 3-node hyperedges at u: those holding w give T; when there are at
+    // most kThreads of them, each thread keeps the other pair of its own for
+    // the second term (below) instead of reading it again
+    const bool one_round = u1 - u0 <= kThreads;
+    uint32_t own_x = 0xFFFFFFFFu, own_y = 0xFFFFFFFFu;
     for (uint32_t p = u0 + tid; p < u1; p += kThreads) {
       const uint32_t* t = v.e3 + 3ull * v.i3_idx[p];
-      if (t[0] == w || t[1] == w || t[2] == w) {
-        const uint32_t c = t[0] ^ t[1] ^ t[2] ^ u ^ w;
+      const uint32_t t0 = t[0], t1 = t[1], t2 = t[2];
+      if (t0 == w || t1 == w || t2 == w) {
+        const uint32_t c = t0 ^ t1 ^ t2 ^ u ^ w;
         atomicOr(&L.XS[c >> 5], 1u << (c & 31));
+      } else {
+        own_x = t0 == u ? t1 : t0;
+        own_y = t2 == u ? t1 : t2;
       }
     }
     __syncthreads();
@@ -721,26 +730,39 @@ __device__ void sample_j2_k4_bits(const View& v, const Draws& d, uint32_t part, 
 #pragma unroll
       for (int j = 0; j < 7; ++j) acc[c][j] = 0;
     const uint32_t n_tasks = nA * W;
-    for (uint32_t t = tid; t < n_tasks; t += kThreads) {
-      const uint32_t xi = t / W, wd = t - xi * W;
-      const uint32_t x = L.xs[xi];
-      const uint32_t xc = node_bit(L.RU, x) | (node_bit(L.RW, x) << 1);
-      const uint32_t rx = bits[uint64_t(x) * W + wd];
-      const uint32_t ru = L.RU[wd], rw = L.RW[wd];
-      const uint32_t yA = L.AS[wd] & mask_gt(x, wd);
-      const uint32_t m10 = yA & ru & ~rw, m01 = yA & ~ru & rw, m11 = yA & ru & rw;
-      uint32_t c7[7];
-      c7[0] = __popc(m10 & ~rx);
-      c7[1] = __popc(m10 & rx);
-      c7[2] = __popc(m01 & ~rx);
-      c7[3] = __popc(m01 & rx);
-      c7[4] = __popc(m11 & ~rx);
-      c7[5] = __popc(m11 & rx);
-      c7[6] = __popc(rx & ~(ru | rw | L.XS[wd]));
+    // two tasks per round, their row words loaded together
+    for (uint32_t t0 = tid; t0 < n_tasks; t0 += 2 * kThreads) {
+      uint32_t rxs[2];
 #pragma unroll
-      for (int c = 0; c < 3; ++c)
+      for (uint32_t k = 0; k < 2; ++k) {
+        const uint32_t t = t0 + k * kThreads;
+        const uint32_t xi = t < n_tasks ? t / W : 0u;
+        rxs[k] = t < n_tasks ? bits[uint64_t(L.xs[xi]) * W + (t - xi * W)] : 0u;
+      }
 #pragma unroll
-        for (int j = 0; j < 7; ++j) acc[c][j] += xc == uint32_t(c + 1) ? c7[j] : 0u;
+      for (uint32_t k = 0; k < 2; ++k) {
+        const uint32_t t = t0 + k * kThreads;
+        if (t >= n_tasks) break;
+        const uint32_t xi = t / W, wd = t - xi * W;
+        const uint32_t x = L.xs[xi];
+        const uint32_t xc = node_bit(L.RU, x) | (node_bit(L.RW, x) << 1);
+        const uint32_t rx = rxs[k];
+        const uint32_t ru = L.RU[wd], rw = L.RW[wd];
+        const uint32_t yA = L.AS[wd] & mask_gt(x, wd);
+        const uint32_t m10 = yA & ru & ~rw, m01 = yA & ~ru & rw, m11 = yA & ru & rw;
+        uint32_t c7[7];
+        c7[0] = __popc(m10 & ~rx);
+        c7[1] = __popc(m10 & rx);
+        c7[2] = __popc(m01 & ~rx);
+        c7[3] = __popc(m01 & rx);
+        c7[4] = __popc(m11 & ~rx);
+        c7[5] = __popc(m11 & rx);
+        c7[6] = __popc(rx & ~(ru | rw | L.XS[wd]));
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+          for (int j = 0; j < 7; ++j) acc[c][j] += xc == uint32_t(c + 1) ? c7[j] : 0u;
+      }
     }
     // second term: each pair {x, y} outside X whose set holds a larger hyperedge
     auto remove = [&](uint32_t x, uint32_t y) {
@@ -750,10 +772,14 @@ __device__ void sample_j2_k4_bits(const View& v, const Draws& d, uint32_t part, 
       const uint8_t cls = lut[pat];
       if (cls != 0xFF) atomicAdd(&h[cls], ~0ull);   // minus one
     };
-    for (uint32_t p = u0 + tid; p < u1; p += kThreads) {
-      const uint32_t* t = v.e3 + 3ull * v.i3_idx[p];
-      if (t[0] == w || t[1] == w || t[2] == w) continue;
-      remove(t[0] == u ? t[1] : t[0], t[2] == u ? t[1] : t[2]);
+    if (one_round) {
+      if (own_x != 0xFFFFFFFFu) remove(own_x, own_y);
+    } else {
+      for (uint32_t p = u0 + tid; p < u1; p += kThreads) {
+        const uint32_t* t = v.e3 + 3ull * v.i3_idx[p];
+        if (t[0] == w || t[1] == w || t[2] == w) continue;
+        remove(t[0] == u ? t[1] : t[0], t[2] == u ? t[1] : t[2]);
+      }
     }
     const uint32_t w0 = v.i3_off[w], w1 = v.i3_off[w + 1];
     for (uint32_t p = w0 + tid; p < w1; p += kThreads) {
