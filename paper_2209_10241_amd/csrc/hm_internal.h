@@ -263,6 +263,8 @@ struct hm_graph {
   // of the key's run in pl_keys; pl_mask + 1 slots
   unsigned long long* pl_slot = nullptr;
   unsigned long long pl_mask = 0;
+  // per slot of the index: the common pairwise neighbours of its pair
+  uint32_t* pl_codeg = nullptr;
   // per node, built on first use without bit rows: triangles at the node, sum
   // of its neighbours' degrees, its 3-node hyperedges by pairwise pattern (8)
   unsigned long long* ns_tri = nullptr;

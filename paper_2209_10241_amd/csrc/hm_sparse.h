@@ -35,6 +35,7 @@ struct PairLinks {
   uint64_t n;
   const ulonglong2* slot;
   unsigned long long mask;
+  const uint32_t* codeg;   // per slot: |N(x) n N(y)| in the pairwise graph
 };
 
 // Run [*lo, *lo + *len) of pl.keys holding `key` (empty when absent).
@@ -53,6 +54,15 @@ __device__ inline void pl_find(const PairLinks& pl, unsigned long long key, uint
     if (s.x == kEmpty64) return;
     h = (h + 1) & pl.mask;
   }
+}
+
+// The number of common pairwise neighbours of x < y, a pair inside some
+// 3-node hyperedge (so present in the index).
+__device__ inline uint32_t pl_codeg(const PairLinks& pl, uint32_t x, uint32_t y) {
+  const unsigned long long key = ((unsigned long long)x << 32) | y;
+  unsigned long long h = mix64(key) & pl.mask;
+  while (pl.slot[h].x != key) h = (h + 1) & pl.mask;
+  return pl.codeg[h];
 }
 
 __device__ inline uint32_t deg2_of(const View& v, uint32_t x) { return v.g2_off[x + 1] - v.g2_off[x]; }
@@ -115,11 +125,10 @@ __device__ __forceinline__ B4Ctx b4_ctx(const View& v, const PairLinks& pl, uint
 }
 
 // Number of nodes v outside e per pairwise combination (av | bv<<1 | cv<<2),
-// exceptional ones included, valid in every lane: the smallest row against
-// the other two members and the smaller of the remaining two rows against the
-// last member, in one lane-strided range; inclusion-exclusion with the
-// members of e removed.
-__device__ __forceinline__ void b4_combo_counts(const View& v, const B4Ctx& x, uint32_t n[8]) {
+// exceptional ones included, valid in every lane: the smallest row walked
+// against the other two members, the common neighbours of those two from
+// the pair index; inclusion-exclusion with the members of e removed.
+__device__ __forceinline__ void b4_combo_counts(const View& v, const PairLinks& pl, const B4Ctx& x, uint32_t n[8]) {
   const int lane = threadIdx.x & (kWave - 1);
   const uint32_t a = x.a, b = x.b, c = x.c;
   const uint32_t pab = x.base_p & 1u, pac = (x.base_p >> 1) & 1u, pbc = (x.base_p >> 2) & 1u;
@@ -135,24 +144,20 @@ __device__ __forceinline__ void b4_combo_counts(const View& v, const B4Ctx& x, u
     r1 = c; x1 = a; y1 = b;
     r2 = da <= db ? a : b; x2 = da <= db ? b : a;
   }
-  uint32_t n1x = 0, n1y = 0, n1xy = 0, n2x = 0;
+  uint32_t n1x = 0, n1y = 0, n1xy = 0;
   const uint32_t b1 = v.g2_off[r1], l1 = v.g2_off[r1 + 1] - b1;
-  const uint32_t b2 = v.g2_off[r2], l2 = v.g2_off[r2 + 1] - b2;
-  for (uint32_t t = lane; t < l1 + l2; t += kWave) {
-    if (t < l1) {
-      const uint32_t z = v.g2_adj[b1 + t];
-      const uint32_t hx = has2(v.hs2, x1, z), hy = has2(v.hs2, y1, z);
-      n1x += hx;
-      n1y += hy;
-      n1xy += hx & hy;
-    } else {
-      n2x += has2(v.hs2, x2, v.g2_adj[b2 + (t - l1)]);
-    }
+  for (uint32_t t = lane; t < l1; t += kWave) {
+    const uint32_t z = v.g2_adj[b1 + t];
+    const Probe64 px = probe2_start(v.hs2, x1, z), py = probe2_start(v.hs2, y1, z);
+    const uint32_t hx = probe64_end(v.hs2, px), hy = probe64_end(v.hs2, py);
+    n1x += hx;
+    n1y += hy;
+    n1xy += hx & hy;
   }
   n1x = wave_sum_u32(n1x);
   n1y = wave_sum_u32(n1y);
   n1xy = wave_sum_u32(n1xy);
-  n2x = wave_sum_u32(n2x);
+  const uint32_t n2x = pl_codeg(pl, min(r2, x2), max(r2, x2));
   const uint32_t tri = n1xy;
   uint32_t cab, cac, cbc;
   if (r1 == a) { cab = n1x; cac = n1y; cbc = n2x; }
@@ -261,7 +266,7 @@ __device__ void b4_sparse(const View& v, const PairLinks& pl, uint32_t a, uint32
   const int lane = threadIdx.x & (kWave - 1);
   const B4Ctx x = b4_ctx(v, pl, a, b, c);
   uint32_t n[8];
-  b4_combo_counts(v, x, n);
+  b4_combo_counts(v, pl, x, n);
   // exceptional nodes, in one lane-strided range; per lane, the number of
   // them in each pairwise combination
   uint32_t dn1 = 0, dn2 = 0, dn3 = 0, dn4 = 0, dn5 = 0, dn6 = 0, dn7 = 0;

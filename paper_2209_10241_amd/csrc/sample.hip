@@ -154,7 +154,7 @@ __device__ void sample_j3_k4(const View& v, const PairLinks& pl, const Queue& q,
     } else {
       const B4Ctx x = b4_ctx(v, pl, a, b, c);
       uint32_t n[8];
-      b4_combo_counts(v, x, n);
+      b4_combo_counts(v, pl, x, n);
       if (lane == 0) {
 #pragma unroll
         for (uint32_t cmb = 1; cmb < 8; ++cmb)
@@ -1066,6 +1066,7 @@ int launch_sampled(const hm_graph* H, int k, const uint32_t* const idx[5], const
   a.pl.n = H->pl_keys ? 3 * H->n_by_size[3] : 0;
   a.pl.slot = reinterpret_cast<const ulonglong2*>(H->pl_slot);
   a.pl.mask = H->pl_mask;
+  a.pl.codeg = H->pl_codeg;
   a.ns.tri = H->ns_tri;
   a.ns.nbr = H->ns_nbr;
   a.ns.h3 = H->ns_h3;

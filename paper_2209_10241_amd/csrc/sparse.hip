@@ -375,6 +375,39 @@ __global__ void k_pl_index_counts(const unsigned long long* __restrict__ keys, u
   }
 }
 
+// Common pairwise neighbours of every distinct pair of the index, into the
+// pair's slot: each wavefront takes 64 positions of the sorted keys at a
+// time and, for each run that starts among them, walks the shorter of the two
+// rows and probes the other.
+__global__ void k_pl_codeg(View v, const unsigned long long* __restrict__ keys, uint64_t n,
+                           const unsigned long long* __restrict__ slot, unsigned long long mask,
+                           uint32_t* __restrict__ codeg) {
+  const uint32_t lane = threadIdx.x & (kWave - 1);
+  const uint64_t wave = (uint64_t(blockIdx.x) * blockDim.x + threadIdx.x) / kWave;
+  const uint64_t n_waves = uint64_t(gridDim.x) * blockDim.x / kWave;
+  for (uint64_t p0 = wave * kWave; p0 < n; p0 += n_waves * kWave) {
+    const uint64_t p = p0 + lane;
+    const bool start = p < n && (p == 0 || keys[p - 1] != keys[p]);
+    unsigned long long m = __ballot(start);
+    while (m) {
+      const uint32_t l = uint32_t(__ffsll(m) - 1);
+      m &= m - 1;
+      const unsigned long long key = keys[p0 + l];
+      const uint32_t x = uint32_t(key >> 32), y = uint32_t(key);
+      const uint32_t dx = deg2_of(v, x), dy = deg2_of(v, y);
+      const uint32_t sn = dx <= dy ? x : y, on = dx <= dy ? y : x;
+      uint32_t c = 0;
+      for (uint32_t q = v.g2_off[sn] + lane; q < v.g2_off[sn + 1]; q += kWave) c += has2(v.hs2, on, v.g2_adj[q]);
+      c = wave_sum_u32(c);
+      if (lane == 0) {
+        unsigned long long h = mix64(key) & mask;
+        while (slot[2 * h] != key) h = (h + 1) & mask;
+        codeg[h] = c;
+      }
+    }
+  }
+}
+
 struct Scratch {
   std::vector<void*> ptrs;
   ~Scratch() {
@@ -552,8 +585,9 @@ int ensure_pair_links(hm_graph* H, hipStream_t st) {
                           static_cast<unsigned long long*>(kt), static_cast<uint32_t*>(et), n, 32 + bits, st);
   // the index: at most n distinct keys, load at most 1/2
   const unsigned long long cap = pow2_capacity(n);
-  void* slots = nullptr;
+  void *slots = nullptr, *codeg = nullptr;
   if (rc == HM_OK) rc = dalloc(&slots, 2 * cap * sizeof(unsigned long long));
+  if (rc == HM_OK) rc = dalloc(&codeg, cap * sizeof(uint32_t));
   if (rc == HM_OK) rc = fill_u64(static_cast<unsigned long long*>(slots), kEmpty64, 2 * cap, st);
   if (rc == HM_OK) {
     const unsigned g = grid_cap(n, 256, 4096);
@@ -561,6 +595,9 @@ int ensure_pair_links(hm_graph* H, hipStream_t st) {
                                          static_cast<unsigned long long*>(slots), cap - 1);
     k_pl_index_counts<<<g, 256, 0, st>>>(static_cast<const unsigned long long*>(k), n,
                                          static_cast<unsigned long long*>(slots), cap - 1);
+    k_pl_codeg<<<grid_cap((n + kWave - 1) / kWave, kWavesPerBlock, 4096), kThreads, 0, st>>>(
+        view_of(H), static_cast<const unsigned long long*>(k), n, static_cast<const unsigned long long*>(slots),
+        cap - 1, static_cast<uint32_t*>(codeg));
     if (hipGetLastError() != hipSuccess) rc = HM_EDEVICE;
   }
   if (rc == HM_OK && hipStreamSynchronize(st) != hipSuccess) rc = HM_EDEVICE;
@@ -570,12 +607,14 @@ int ensure_pair_links(hm_graph* H, hipStream_t st) {
     dfree(k);
     dfree(e);
     dfree(slots);
+    dfree(codeg);
     return rc;
   }
   H->pl_keys = static_cast<unsigned long long*>(k);
   H->pl_edge = static_cast<uint32_t*>(e);
   H->pl_slot = static_cast<unsigned long long*>(slots);
   H->pl_mask = cap - 1;
+  H->pl_codeg = static_cast<uint32_t*>(codeg);
   return HM_OK;
 }
 
@@ -586,6 +625,7 @@ PairLinks pair_links_of(const hm_graph* H) {
   pl.n = H->pl_keys ? 3 * H->n_by_size[3] : 0;
   pl.slot = reinterpret_cast<const ulonglong2*>(H->pl_slot);
   pl.mask = H->pl_mask;
+  pl.codeg = H->pl_codeg;
   return pl;
 }
 
