@@ -52,13 +52,16 @@ __device__ inline bool probe64_end(const Set64& s, Probe64 p) {
     p.v = s.slot[p.pos];
   }
 }
-__device__ inline Probe128 probe3_start(const Set128& s, uint32_t a, uint32_t b, uint32_t c) {
-  sort3(a, b, c);
+__device__ inline Probe128 probe128_start(const Set128& s, Key128 key) {
   Probe128 p;
-  p.key = key3(a, b, c);
-  p.pos = hash128(p.key) & s.mask;
+  p.key = key;
+  p.pos = hash128(key) & s.mask;
   p.v = *reinterpret_cast<const ulonglong2*>(s.slot + 2 * p.pos);
   return p;
+}
+__device__ inline Probe128 probe3_start(const Set128& s, uint32_t a, uint32_t b, uint32_t c) {
+  sort3(a, b, c);
+  return probe128_start(s, key3(a, b, c));
 }
 __device__ inline bool probe128_end(const Set128& s, Probe128 p) {
   while (true) {

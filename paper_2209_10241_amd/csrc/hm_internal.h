@@ -265,6 +265,10 @@ struct hm_graph {
   unsigned long long pl_mask = 0;
   // per slot of the index: the common pairwise neighbours of its pair
   uint32_t* pl_codeg = nullptr;
+  // per pair entry: the third node of its hyperedge, and that node's pairwise
+  // adjacency to the pair's two nodes (bits 0 and 1)
+  uint32_t* pl_third = nullptr;
+  uint8_t* pl_adj = nullptr;
   // per node, built on first use without bit rows: triangles at the node, sum
   // of its neighbours' degrees, its 3-node hyperedges by pairwise pattern (8)
   unsigned long long* ns_tri = nullptr;

@@ -36,6 +36,10 @@ struct PairLinks {
   const ulonglong2* slot;
   unsigned long long mask;
   const uint32_t* codeg;   // per slot: |N(x) n N(y)| in the pairwise graph
+  // per entry: the third node t of its 3-node hyperedge, and t's pairwise
+  // adjacency to the key's nodes (bit 0: x ~ t, bit 1: y ~ t)
+  const uint32_t* third;
+  const uint8_t* adj;
 };
 
 // Run [*lo, *lo + *len) of pl.keys holding `key` (empty when absent).
@@ -200,22 +204,11 @@ __device__ __forceinline__ uint32_t b4_exception(const View& v, const PairLinks&
     slot = 3;
     p = x.lo3 + (t - x.len0 - x.len1 - x.len2);
   }
-  uint32_t y;
-  uint32_t abv = 0, acv = 0, bcv = 0, quad = 0;
+  uint32_t y, pair_adj = 0;
   if (slot < 3) {
-    const uint32_t q0 = slot < 2 ? a : b, q1 = slot == 0 ? b : c;
-    const uint32_t* f = v.e3 + 3ull * pl.edge[p];
-    y = f[0] ^ f[1] ^ f[2] ^ q0 ^ q1;
+    y = pl.third[p];
     if (y == a || y == b || y == c) return 0;   // e itself
-    if (slot == 0) {
-      abv = 1;
-    } else if (slot == 1) {
-      if (has3(v.hs3, a, b, y)) return 0;
-      acv = 1;
-    } else {
-      if (has3(v.hs3, a, b, y) || has3(v.hs3, a, c, y)) return 0;
-      bcv = 1;
-    }
+    pair_adj = pl.adj[p];
   } else {
     const uint32_t* f = v.e4 + 4ull * v.i4_idx[p];
     const uint32_t f0 = f[0], f1 = f[1], f2 = f[2], f3 = f[3];
@@ -223,21 +216,38 @@ __device__ __forceinline__ uint32_t b4_exception(const View& v, const PairLinks&
                          uint32_t(f2 == a || f2 == b || f2 == c) + uint32_t(f3 == a || f3 == b || f3 == c);
     if (hit != 3) return 0;
     y = f0 ^ f1 ^ f2 ^ f3 ^ a ^ b ^ c;
-    if (has3(v.hs3, a, b, y) || has3(v.hs3, a, c, y) || has3(v.hs3, b, c, y)) return 0;
-    quad = 1;
   }
-  // fill-in of e u {y}
-  if (slot <= 0) acv = has3(v.hs3, a, c, y);
-  if (slot <= 1) bcv = has3(v.hs3, b, c, y);
+  // Every membership test the set e u {y} needs, issued together: the
+  // 3-node sets through y not already known from the slot, the 4-node set
+  // (unless the slot is the 4-node hyperedges'), y's pairs with a, b, c.
+  Probe128 pab, pac, pbc, pq;
+  if (slot != 0) pab = probe3_start(v.hs3, a, b, y);
+  if (slot != 1) pac = probe3_start(v.hs3, a, c, y);
+  if (slot != 2) pbc = probe3_start(v.hs3, b, c, y);
   if (slot < 3) {
     uint32_t s0 = a, s1 = b, s2 = c, s3 = y;
     // ascending 4-tuple for the 4-node probe
     if (s3 < s2) { const uint32_t tt = s2; s2 = s3; s3 = tt; }
     if (s2 < s1) { const uint32_t tt = s1; s1 = s2; s2 = tt; }
     if (s1 < s0) { const uint32_t tt = s0; s0 = s1; s1 = tt; }
-    quad = set128_has(v.hs4, key4(s0, s1, s2, s3));
+    pq = probe128_start(v.hs4, key4(s0, s1, s2, s3));
   }
-  const uint32_t av = has2(v.hs2, a, y), bv = has2(v.hs2, b, y), cv = has2(v.hs2, c, y);
+  // y's pairs with the two members of the slot's pair come with the entry
+  Probe64 pa, pb, pc;
+  if (slot == 2 || slot == 3) pa = probe2_start(v.hs2, a, y);
+  if (slot == 1 || slot == 3) pb = probe2_start(v.hs2, b, y);
+  if (slot == 0 || slot == 3) pc = probe2_start(v.hs2, c, y);
+  const uint32_t abv = slot == 0 ? 1u : uint32_t(probe128_end(v.hs3, pab));
+  const uint32_t acv = slot == 1 ? 1u : uint32_t(probe128_end(v.hs3, pac));
+  const uint32_t bcv = slot == 2 ? 1u : uint32_t(probe128_end(v.hs3, pbc));
+  // each exceptional node once: a 3-node hyperedge of an earlier slot takes it
+  if (slot == 1 && abv) return 0;
+  if (slot == 2 && (abv || acv)) return 0;
+  if (slot == 3 && (abv || acv || bcv)) return 0;
+  const uint32_t quad = slot == 3 ? 1u : uint32_t(probe128_end(v.hs4, pq));
+  const uint32_t av = slot == 0 || slot == 1 ? (pair_adj & 1u) : uint32_t(probe64_end(v.hs2, pa));
+  const uint32_t bv = slot == 0 ? (pair_adj >> 1) : (slot == 2 ? (pair_adj & 1u) : uint32_t(probe64_end(v.hs2, pb)));
+  const uint32_t cv = slot == 1 || slot == 2 ? (pair_adj >> 1) : uint32_t(probe64_end(v.hs2, pc));
   const uint32_t combo = av | (bv << 1) | (cv << 2);
   bool counted = !quad;   // a 4-node hyperedge: counted on its own, or larger than a sampled 3-node one
   if (OWN && counted) {

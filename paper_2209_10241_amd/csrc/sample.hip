@@ -317,8 +317,7 @@ __device__ inline uint32_t j2_cls(const View& v, const J2Ctx& c, uint32_t y) {
   return has2(v.hs2, c.s, y) | (has2(v.hs2, c.o, y) << 1);
 }
 __device__ inline uint32_t j2_t_node(const View& v, const PairLinks& pl, const J2Ctx& c, uint64_t p) {
-  const uint32_t* f = v.e3 + 3ull * pl.edge[p];
-  return f[0] ^ f[1] ^ f[2] ^ c.s ^ c.o;
+  return pl.third[p];
 }
 // a pair {x, y} outside X whose set holds a larger hyperedge, taken off
 __device__ inline void j2_remove(const View& v, const J2Ctx& c, const uint8_t* lut, unsigned long long* h, uint32_t x,
@@ -461,15 +460,16 @@ __device__ void j2_walk_r(const View& v, const PairLinks& pl, const J2Ctx& c, ui
       [&](uint32_t slot, uint32_t, uint32_t r) {
         const uint32_t y = L.cnt[slot][0], fy = L.cnt[slot][1];
         const uint32_t sy = fy & 1u, oy = (fy >> 1) & 1u, ty = fy >> 2;
-        const uint32_t* f = v.e3 + 3ull * pl.edge[r];
-        const uint32_t z = f[0] ^ f[1] ^ f[2] ^ c.o ^ y;
+        const uint32_t z = pl.third[r];
         if (z == c.s) return;   // an {s, o, t}
-        const Probe64 psz = probe2_start(v.hs2, c.s, z), poz = probe2_start(v.hs2, c.o, z),
-                      pyz = probe2_start(v.hs2, y, z);
+        // o ~ z and y ~ z come with the entry (its key is the pair {o, y})
+        const uint32_t za = pl.adj[r];
+        const uint32_t oz = c.o < y ? (za & 1u) : (za >> 1), yz = c.o < y ? (za >> 1) : (za & 1u);
+        const Probe64 psz = probe2_start(v.hs2, c.s, z);
         const Probe128 psyz = probe3_start(v.hs3, c.s, y, z);
         Probe128 ptz;
         if (c.any_t) ptz = probe3_start(v.hs3, c.s, c.o, z);
-        const uint32_t sz = probe64_end(v.hs2, psz), oz = probe64_end(v.hs2, poz), yz = probe64_end(v.hs2, pyz);
+        const uint32_t sz = probe64_end(v.hs2, psz);
         const uint32_t tz = c.any_t && probe128_end(v.hs3, ptz);
         if (z < y && (sz | tz)) return;   // taken from z
         // as the histogram at o counts it (the smaller node first)
@@ -1067,6 +1067,8 @@ int launch_sampled(const hm_graph* H, int k, const uint32_t* const idx[5], const
   a.pl.slot = reinterpret_cast<const ulonglong2*>(H->pl_slot);
   a.pl.mask = H->pl_mask;
   a.pl.codeg = H->pl_codeg;
+  a.pl.third = H->pl_third;
+  a.pl.adj = H->pl_adj;
   a.ns.tri = H->ns_tri;
   a.ns.nbr = H->ns_nbr;
   a.ns.h3 = H->ns_h3;

@@ -375,6 +375,21 @@ __global__ void k_pl_index_counts(const unsigned long long* __restrict__ keys, u
   }
 }
 
+// Per pair entry: the third node of its 3-node hyperedge and that node's
+// pairwise adjacency to the two nodes of the key.
+__global__ void k_pl_third(const uint32_t* __restrict__ e3, const unsigned long long* __restrict__ keys,
+                           const uint32_t* __restrict__ edge, uint64_t n, Set64 hs2, uint32_t* __restrict__ third,
+                           uint8_t* __restrict__ adj) {
+  for (uint64_t p = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; p < n; p += uint64_t(gridDim.x) * blockDim.x) {
+    const unsigned long long key = keys[p];
+    const uint32_t x = uint32_t(key >> 32), y = uint32_t(key);
+    const uint32_t* f = e3 + 3ull * edge[p];
+    const uint32_t t = f[0] ^ f[1] ^ f[2] ^ x ^ y;
+    third[p] = t;
+    adj[p] = uint8_t(uint32_t(has2(hs2, x, t)) | (uint32_t(has2(hs2, y, t)) << 1));
+  }
+}
+
 // Common pairwise neighbours of every distinct pair of the index, into the
 // pair's slot: each wavefront takes 64 positions of the sorted keys at a
 // time and, for each run that starts among them, walks the shorter of the two
@@ -585,9 +600,11 @@ int ensure_pair_links(hm_graph* H, hipStream_t st) {
                           static_cast<unsigned long long*>(kt), static_cast<uint32_t*>(et), n, 32 + bits, st);
   // the index: at most n distinct keys, load at most 1/2
   const unsigned long long cap = pow2_capacity(n);
-  void *slots = nullptr, *codeg = nullptr;
+  void *slots = nullptr, *codeg = nullptr, *third = nullptr, *adj = nullptr;
   if (rc == HM_OK) rc = dalloc(&slots, 2 * cap * sizeof(unsigned long long));
   if (rc == HM_OK) rc = dalloc(&codeg, cap * sizeof(uint32_t));
+  if (rc == HM_OK) rc = dalloc(&third, n * sizeof(uint32_t));
+  if (rc == HM_OK) rc = dalloc(&adj, n * sizeof(uint8_t));
   if (rc == HM_OK) rc = fill_u64(static_cast<unsigned long long*>(slots), kEmpty64, 2 * cap, st);
   if (rc == HM_OK) {
     const unsigned g = grid_cap(n, 256, 4096);
@@ -595,6 +612,8 @@ int ensure_pair_links(hm_graph* H, hipStream_t st) {
                                          static_cast<unsigned long long*>(slots), cap - 1);
     k_pl_index_counts<<<g, 256, 0, st>>>(static_cast<const unsigned long long*>(k), n,
                                          static_cast<unsigned long long*>(slots), cap - 1);
+    k_pl_third<<<g, 256, 0, st>>>(H->e3, static_cast<const unsigned long long*>(k), static_cast<const uint32_t*>(e), n,
+                                  H->hs2, static_cast<uint32_t*>(third), static_cast<uint8_t*>(adj));
     k_pl_codeg<<<grid_cap((n + kWave - 1) / kWave, kWavesPerBlock, 4096), kThreads, 0, st>>>(
         view_of(H), static_cast<const unsigned long long*>(k), n, static_cast<const unsigned long long*>(slots),
         cap - 1, static_cast<uint32_t*>(codeg));
@@ -608,6 +627,8 @@ int ensure_pair_links(hm_graph* H, hipStream_t st) {
     dfree(e);
     dfree(slots);
     dfree(codeg);
+    dfree(third);
+    dfree(adj);
     return rc;
   }
   H->pl_keys = static_cast<unsigned long long*>(k);
@@ -615,6 +636,8 @@ int ensure_pair_links(hm_graph* H, hipStream_t st) {
   H->pl_slot = static_cast<unsigned long long*>(slots);
   H->pl_mask = cap - 1;
   H->pl_codeg = static_cast<uint32_t*>(codeg);
+  H->pl_third = static_cast<uint32_t*>(third);
+  H->pl_adj = static_cast<uint8_t*>(adj);
   return HM_OK;
 }
 
@@ -626,6 +649,8 @@ PairLinks pair_links_of(const hm_graph* H) {
   pl.slot = reinterpret_cast<const ulonglong2*>(H->pl_slot);
   pl.mask = H->pl_mask;
   pl.codeg = H->pl_codeg;
+  pl.third = H->pl_third;
+  pl.adj = H->pl_adj;
   return pl;
 }
 
