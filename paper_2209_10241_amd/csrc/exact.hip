@@ -91,6 +91,9 @@ __global__ void k_combine(unsigned long long* __restrict__ hist, int n_classes, 
 // the counts afterwards (a kernel boundary, rather than a device-wide fence
 // in every workgroup, makes the atomics of all workgroups visible to it).
 constexpr uint32_t kA4Chunk = kWave;   // 4-node hyperedges per wavefront item
+// Largest bit matrix and row starts a workgroup copies into LDS (about 500
+// nodes): several workgroups per CU still fit beside them.
+constexpr size_t kLdsBitsMaxBytes = 40960;
 
 struct ExactArgs {
   View v;
@@ -101,18 +104,43 @@ struct ExactArgs {
 
 // Order 4: items [0, n2) are the pairs of G2 (case (c)), [n2, n2 + n3) the
 // 3-node hyperedges (case (b)), then chunks of kA4Chunk 4-node hyperedges
-// (case (a)).  Dynamic LDS holds b4_set_words(W) words per wavefront.
+// (case (a)).  Dynamic LDS holds b4_set_words(W) words per wavefront and,
+// with LB, a copy of the whole bit matrix (N x W words) and of the row
+// starts of G2 and of the incidence lists, so that every adjacency word and
+// row bound the items read comes from LDS rather than from L2.
+template <bool LB>
 __global__ void __launch_bounds__(kThreads) k_exact4_bits(ExactArgs a) {
   __shared__ uint8_t lut[2048];
   __shared__ unsigned long long h_main[256], h_sub[256], h_g2[256];
   __shared__ uint32_t ylist[kWavesPerBlock][kWave];
-  extern __shared__ uint32_t b4_sets[];
+  extern __shared__ uint32_t dyn_lds[];
+  View v = a.v;
+  uint32_t* b4_sets = dyn_lds;
+  if (LB) {
+    // the rows start 16 * W words in: 16-byte aligned
+    uint32_t* rows = dyn_lds + kWavesPerBlock * b4_set_words(v.W);
+    const uint32_t n = v.N * v.W, n4 = n / 4;
+    const uint4* src = reinterpret_cast<const uint4*>(v.bits);
+    uint4* dst = reinterpret_cast<uint4*>(rows);
+    for (uint32_t i = threadIdx.x; i < n4; i += kThreads) dst[i] = src[i];
+    for (uint32_t i = 4 * n4 + threadIdx.x; i < n; i += kThreads) rows[i] = v.bits[i];
+    // and the row starts of G2 and of the incidence lists
+    uint32_t* offs = rows + n;
+    for (uint32_t i = threadIdx.x; i <= v.N; i += kThreads) {
+      offs[i] = v.g2_off[i];
+      offs[v.N + 1 + i] = v.i3_off[i];
+      offs[2 * (v.N + 1) + i] = v.i4_off[i];
+    }
+    v.bits = rows;
+    v.g2_off = offs;
+    v.i3_off = offs + v.N + 1;
+    v.i4_off = offs + 2 * (v.N + 1);
+  }
   load_lut(lut, a.lut, 2048);
   h_main[threadIdx.x] = 0;
   h_sub[threadIdx.x] = 0;
   h_g2[threadIdx.x] = 0;
   __syncthreads();
-  const View& v = a.v;
   const int wv = threadIdx.x / kWave;
   const uint32_t lane = threadIdx.x & (kWave - 1);
   uint32_t* sets = b4_sets + wv * b4_set_words(v.W);
@@ -251,11 +279,18 @@ int count_exact_impl(const hm_graph* H, int k, int64_t* counts, hipStream_t st) 
     a.lut = k == 4 ? lut4 : lut3;
     a.hist = H->hist;
     if (k == 4) {
-      const size_t lds = size_t(kWavesPerBlock) * b4_set_words(v.W) * 4;
+      const size_t rows = (size_t(v.N) * v.W + 3 * (size_t(v.N) + 1)) * 4;
+      const bool lb = rows <= kLdsBitsMaxBytes;
+      const size_t lds = size_t(kWavesPerBlock) * b4_set_words(v.W) * 4 + (lb ? rows : 0);
       const uint64_t items = n2 + n3 + (n4 + kA4Chunk - 1) / kA4Chunk;
-      const unsigned grid = fused_grid(reinterpret_cast<const void*>(k_exact4_bits), lds, items, kWavesPerBlock);
+      const void* kern = lb ? reinterpret_cast<const void*>(k_exact4_bits<true>)
+                            : reinterpret_cast<const void*>(k_exact4_bits<false>);
+      const unsigned grid = fused_grid(kern, lds, items, kWavesPerBlock);
       ProfileScope ps("k_exact4_bits", st);
-      k_exact4_bits<<<grid, kThreads, lds, st>>>(a);
+      if (lb)
+        k_exact4_bits<true><<<grid, kThreads, lds, st>>>(a);
+      else
+        k_exact4_bits<false><<<grid, kThreads, lds, st>>>(a);
     } else {
       const unsigned grid = fused_grid(reinterpret_cast<const void*>(k_exact3_bits), 0, n2 * v.W + n3, kThreads);
       ProfileScope ps("k_exact3_bits", st);

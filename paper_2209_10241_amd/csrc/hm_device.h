@@ -103,21 +103,46 @@ __device__ inline uint32_t upper_bound(const uint32_t* adj, uint32_t p, uint32_t
   }
   return p;
 }
-__device__ inline uint32_t wave_sum_u32(uint32_t x) {
-#pragma unroll
-  for (int o = kWave / 2; o > 0; o >>= 1) x += __shfl_xor(x, o, kWave);
-  return x;
+// Wavefront sums with data-parallel-primitive moves (no LDS round trips):
+// shifts right by 1, 2, 4 and 8 lanes within each row of 16 leave a row's
+// total in its last lane; the broadcasts of lane 15 into rows 1 and 3 and of
+// lane 31 into rows 2 and 3 then leave the wavefront's total in lane 63,
+// which is read into a scalar.  Lanes shifted in from outside a row read 0.
+// Every lane of the wavefront must be active.
+namespace dpp {
+constexpr int kRowShr1 = 0x111, kRowShr2 = 0x112, kRowShr4 = 0x114, kRowShr8 = 0x118;
+constexpr int kRowBcast15 = 0x142, kRowBcast31 = 0x143;
+template <int CTRL, int ROWS>
+__device__ __forceinline__ uint32_t mov(uint32_t x) {
+  return uint32_t(__builtin_amdgcn_update_dpp(0, int(x), CTRL, ROWS, 0xF, true));
 }
+}  // namespace dpp
+
+__device__ inline uint32_t wave_sum_u32(uint32_t x) {
+  x += dpp::mov<dpp::kRowShr1, 0xF>(x);
+  x += dpp::mov<dpp::kRowShr2, 0xF>(x);
+  x += dpp::mov<dpp::kRowShr4, 0xF>(x);
+  x += dpp::mov<dpp::kRowShr8, 0xF>(x);
+  x += dpp::mov<dpp::kRowBcast15, 0xA>(x);
+  x += dpp::mov<dpp::kRowBcast31, 0xC>(x);
+  return uint32_t(__builtin_amdgcn_readlane(int(x), kWave - 1));
+}
+
+template <int CTRL, int ROWS>
+__device__ __forceinline__ unsigned long long dpp_add64(unsigned long long v) {
+  const uint32_t lo = dpp::mov<CTRL, ROWS>(uint32_t(v)), hi = dpp::mov<CTRL, ROWS>(uint32_t(v >> 32));
+  return v + ((unsigned long long)hi << 32 | lo);
+}
+
 __device__ inline unsigned long long wave_sum(unsigned long long v) {
-  uint32_t lo = uint32_t(v), hi = uint32_t(v >> 32);
-#pragma unroll
-  for (int d = kWave / 2; d > 0; d >>= 1) {
-    uint32_t olo = __shfl_xor(lo, d, kWave);
-    uint32_t ohi = __shfl_xor(hi, d, kWave);
-    unsigned long long s = ((unsigned long long)hi << 32 | lo) + ((unsigned long long)ohi << 32 | olo);
-    lo = uint32_t(s);
-    hi = uint32_t(s >> 32);
-  }
+  v = dpp_add64<dpp::kRowShr1, 0xF>(v);
+  v = dpp_add64<dpp::kRowShr2, 0xF>(v);
+  v = dpp_add64<dpp::kRowShr4, 0xF>(v);
+  v = dpp_add64<dpp::kRowShr8, 0xF>(v);
+  v = dpp_add64<dpp::kRowBcast15, 0xA>(v);
+  v = dpp_add64<dpp::kRowBcast31, 0xC>(v);
+  const uint32_t lo = uint32_t(__builtin_amdgcn_readlane(int(uint32_t(v)), kWave - 1));
+  const uint32_t hi = uint32_t(__builtin_amdgcn_readlane(int(uint32_t(v >> 32)), kWave - 1));
   return (unsigned long long)hi << 32 | lo;
 }
 
