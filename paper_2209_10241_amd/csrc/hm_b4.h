@@ -105,8 +105,8 @@ __device__ void b4_edge_hash(uint32_t a, uint32_t b, uint32_t c, const uint32_t*
 // Bit-row version, counting instead of listing.  The wavefront builds, in
 // LDS (sets: 4*W words), bit sets of the nodes v with {a,b,v}, {a,c,v} or
 // {b,c,v} a 3-node hyperedge (T_ab, T_ac, T_bc, from the incident 3-node
-// hyperedges of a and b) and with e u {v} a 4-node hyperedge (Q, from those
-// of a).  Any other v leaves e the only hyperedge of size >= 3 in e u {v}, so
+// hyperedges of the two members with the fewest) and with e u {v} a 4-node
+// hyperedge (Q, from those of the member with the fewest).  Any other v leaves e the only hyperedge of size >= 3 in e u {v}, so
 // those v are counted per pairwise combination (av, bv, cv) with popcounts
 // over the rows of a, b, c; each lane classifies the nodes of its words that
 // lie in a T set and outside Q one by one.
@@ -127,11 +127,17 @@ __device__ void b4_edge_bits_count(uint32_t a, uint32_t b, uint32_t c, const uin
   const uint32_t* Rc = bits + uint64_t(c) * W;
   for (uint32_t w = lane; w < 4 * W; w += kWave) sets[w] = 0;
   wave_sync();
-  // 3-node hyperedges sharing two nodes with e
-  const uint32_t pa = i3_off[a], la = i3_off[a + 1] - pa;
-  const uint32_t pb = i3_off[b], lb = i3_off[b + 1] - pb;
-  for (uint32_t t = lane; t < la + lb; t += kWave) {
-    const uint32_t f = i3_idx[t < la ? pa + t : pb + (t - la)];
+  // 3-node hyperedges sharing two nodes with e: each holds one of any two
+  // members of e, so the lists of the two members with the fewest are read
+  // (one found twice sets its bit twice)
+  const uint32_t la0 = i3_off[a], la = i3_off[a + 1] - la0;
+  const uint32_t lb0 = i3_off[b], lb = i3_off[b + 1] - lb0;
+  const uint32_t lc0 = i3_off[c], lc = i3_off[c + 1] - lc0;
+  const bool skip_a = la >= lb && la >= lc, skip_b = !skip_a && lb >= lc;
+  const uint32_t pa = skip_a ? lb0 : la0, l1 = skip_a ? lb : la;
+  const uint32_t pb = (skip_a || skip_b) ? lc0 : lb0, l2 = (skip_a || skip_b) ? lc : lb;
+  for (uint32_t t = lane; t < l1 + l2; t += kWave) {
+    const uint32_t f = i3_idx[t < l1 ? pa + t : pb + (t - l1)];
     const uint32_t x = e3[3ull * f], y = e3[3ull * f + 1], z = e3[3ull * f + 2];
     const bool ha = (x == a || y == a || z == a), hb = (x == b || y == b || z == b), hc = (x == c || y == c || z == c);
     if (int(ha) + int(hb) + int(hc) != 2) continue;
@@ -139,8 +145,10 @@ __device__ void b4_edge_bits_count(uint32_t a, uint32_t b, uint32_t c, const uin
     uint32_t* T = (ha && hb) ? Tab : (ha ? Tac : Tbc);
     atomicOr(&T[v >> 5], 1u << (v & 31));
   }
-  // 4-node hyperedges containing e
-  const uint32_t p4 = i4_off[a], l4 = i4_off[a + 1] - p4;
+  // 4-node hyperedges containing e, from the shortest list of a member
+  const uint32_t fa = i4_off[a + 1] - i4_off[a], fb = i4_off[b + 1] - i4_off[b], fc = i4_off[c + 1] - i4_off[c];
+  const uint32_t m4 = (fa <= fb && fa <= fc) ? a : (fb <= fc ? b : c);
+  const uint32_t p4 = i4_off[m4], l4 = i4_off[m4 + 1] - p4;
   for (uint32_t t = lane; t < l4; t += kWave) {
     const uint32_t f = i4_idx[p4 + t];
     const uint32_t m0 = e4[4ull * f], m1 = e4[4ull * f + 1], m2 = e4[4ull * f + 2], m3 = e4[4ull * f + 3];
@@ -185,16 +193,12 @@ __device__ void b4_edge_bits_count(uint32_t a, uint32_t b, uint32_t c, const uin
       count_class(lut, h_main, h_sub, pt, kPairBits4);
     }
   }
-  // Reduce over the lanes that hold words (the first min(W, 64)); a
+  // Reduce over the wavefront (lanes without words hold zeros); a
   // combination's total over the wavefront is below the node count, at most
   // 8192, so two of them share a 32-bit word.
   uint32_t pk[4] = {n1 | (n2 << 16), n3 | (n4 << 16), n5 | (n6 << 16), n7};
-  uint32_t width = 1;
-  while (width < W && width < uint32_t(kWave)) width <<= 1;
-  for (uint32_t o = width >> 1; o > 0; o >>= 1) {
 #pragma unroll
-    for (int k = 0; k < 4; ++k) pk[k] += __shfl_xor(pk[k], int(o), kWave);
-  }
+  for (int k = 0; k < 4; ++k) pk[k] = wave_sum_u32(pk[k]);
   uint32_t n[8];
   n[1] = pk[0] & 0xFFFFu; n[2] = pk[0] >> 16; n[3] = pk[1] & 0xFFFFu; n[4] = pk[1] >> 16;
   n[5] = pk[2] & 0xFFFFu; n[6] = pk[2] >> 16; n[7] = pk[3];

@@ -151,15 +151,32 @@ __device__ inline void wave_sync() {
   __builtin_amdgcn_wave_barrier();
 }
 
+// Inclusive prefix sums over the wavefront by the same moves as the sums:
+// after the shifts within rows each lane holds its row's prefix, the
+// broadcasts then add the totals of the rows before it.  Every lane of the
+// wavefront must be active.
+__device__ inline uint32_t wave_inclusive_scan(uint32_t x) {
+  x += dpp::mov<dpp::kRowShr1, 0xF>(x);
+  x += dpp::mov<dpp::kRowShr2, 0xF>(x);
+  x += dpp::mov<dpp::kRowShr4, 0xF>(x);
+  x += dpp::mov<dpp::kRowShr8, 0xF>(x);
+  x += dpp::mov<dpp::kRowBcast15, 0xA>(x);
+  x += dpp::mov<dpp::kRowBcast31, 0xC>(x);
+  return x;
+}
+__device__ inline unsigned long long wave_inclusive_scan(unsigned long long v) {
+  v = dpp_add64<dpp::kRowShr1, 0xF>(v);
+  v = dpp_add64<dpp::kRowShr2, 0xF>(v);
+  v = dpp_add64<dpp::kRowShr4, 0xF>(v);
+  v = dpp_add64<dpp::kRowShr8, 0xF>(v);
+  v = dpp_add64<dpp::kRowBcast15, 0xA>(v);
+  v = dpp_add64<dpp::kRowBcast31, 0xC>(v);
+  return v;
+}
+
 __device__ inline uint32_t wave_exclusive_scan(uint32_t v, uint32_t* total) {
-  const int lane = threadIdx.x & (kWave - 1);
-  uint32_t x = v;
-#pragma unroll
-  for (int d = 1; d < kWave; d <<= 1) {
-    const uint32_t y = __shfl_up(x, d, kWave);
-    if (lane >= d) x += y;
-  }
-  *total = __shfl(x, kWave - 1, kWave);
+  const uint32_t x = wave_inclusive_scan(v);
+  *total = uint32_t(__builtin_amdgcn_readlane(int(x), kWave - 1));
   return x - v;
 }
 

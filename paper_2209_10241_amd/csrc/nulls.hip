@@ -58,12 +58,7 @@ __global__ void k_null_gather(const uint32_t* __restrict__ vals, uint64_t n, uin
 // ---------------------------------------------------------------- block helpers
 __device__ inline uint32_t block_exclusive_scan(uint32_t v, uint32_t* wsum, uint32_t* total) {
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
-  uint32_t x = v;
-#pragma unroll
-  for (int d = 1; d < kWave; d <<= 1) {
-    const uint32_t y = __shfl_up(x, d, kWave);
-    if (lane >= d) x += y;
-  }
+  const uint32_t x = wave_inclusive_scan(v);
   if (lane == kWave - 1) wsum[wave] = x;
   __syncthreads();
   uint32_t before = 0, all = 0;

@@ -2,7 +2,7 @@
 // LSD radix sort of (64-bit key, 32-bit value) pairs and fills.
 #include <algorithm>
 
-#include "hm_internal.h"
+#include "hm_device.h"
 
 namespace hm {
 namespace {
@@ -15,12 +15,7 @@ template <typename T>
 __device__ T block_exclusive_scan(T v, T* wave_sums, T* total) {
   const int lane = threadIdx.x & (kWave - 1);
   const int wave = threadIdx.x / kWave;
-  T x = v;
-#pragma unroll
-  for (int d = 1; d < kWave; d <<= 1) {
-    T y = __shfl_up(x, d, kWave);
-    if (lane >= d) x += y;
-  }
+  const T x = wave_inclusive_scan(v);
   if (lane == kWave - 1) wave_sums[wave] = x;
   __syncthreads();
   T before = 0, all = 0;

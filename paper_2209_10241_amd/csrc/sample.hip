@@ -656,12 +656,6 @@ struct J2Lds {
   uint32_t red[21];
 };
 
-__device__ inline uint32_t wave_sum32(uint32_t x) {
-#pragma unroll
-  for (int o = kWave / 2; o > 0; o >>= 1) x += __shfl_xor(x, o, kWave);
-  return x;
-}
-
 __device__ inline uint32_t node_bit(const uint32_t* row, uint32_t x) { return (row[x >> 5] >> (x & 31)) & 1u; }
 
 __device__ void sample_j2_k4_bits(const View& v, const Draws& d, uint32_t part, uint32_t n_parts, J2Lds& L,
@@ -807,7 +801,7 @@ __device__ void sample_j2_k4_bits(const View& v, const Draws& d, uint32_t part, 
     for (int c = 0; c < 3; ++c)
 #pragma unroll
       for (int j = 0; j < 7; ++j) {
-        const uint32_t sum = wave_sum32(acc[c][j]);
+        const uint32_t sum = wave_sum_u32(acc[c][j]);
         if (lane == 0 && sum) atomicAdd(&L.red[c * 7 + j], sum);
       }
     __syncthreads();
