@@ -95,6 +95,11 @@ constexpr uint32_t kA4Chunk = kWave;   // 4-node hyperedges per wavefront item
 // nodes): several workgroups per CU still fit beside them.
 constexpr size_t kLdsBitsMaxBytes = 40960;
 
+// Workgroups of the order-4 launch: 16 wavefronts, so that the tables it
+// copies into LDS are read once per CU and its counters flushed once per CU.
+constexpr uint32_t kExact4Waves = 16;
+constexpr uint32_t kExact4Threads = kExact4Waves * kWave;
+
 struct ExactArgs {
   View v;
   uint64_t n2, n3, n4;
@@ -109,24 +114,24 @@ struct ExactArgs {
 // starts of G2 and of the incidence lists, so that every adjacency word and
 // row bound the items read comes from LDS rather than from L2.
 template <bool LB>
-__global__ void __launch_bounds__(kThreads) k_exact4_bits(ExactArgs a) {
+__global__ void __launch_bounds__(kExact4Threads) k_exact4_bits(ExactArgs a) {
   __shared__ uint8_t lut[2048];
   __shared__ unsigned long long h_main[256], h_sub[256], h_g2[256];
-  __shared__ uint32_t ylist[kWavesPerBlock][kWave];
+  __shared__ uint32_t ylist[kExact4Waves][kWave];
   extern __shared__ uint32_t dyn_lds[];
   View v = a.v;
   uint32_t* b4_sets = dyn_lds;
   if (LB) {
     // the rows start 16 * W words in: 16-byte aligned
-    uint32_t* rows = dyn_lds + kWavesPerBlock * b4_set_words(v.W);
+    uint32_t* rows = dyn_lds + kExact4Waves * b4_set_words(v.W);
     const uint32_t n = v.N * v.W, n4 = n / 4;
     const uint4* src = reinterpret_cast<const uint4*>(v.bits);
     uint4* dst = reinterpret_cast<uint4*>(rows);
-    for (uint32_t i = threadIdx.x; i < n4; i += kThreads) dst[i] = src[i];
-    for (uint32_t i = 4 * n4 + threadIdx.x; i < n; i += kThreads) rows[i] = v.bits[i];
+    for (uint32_t i = threadIdx.x; i < n4; i += kExact4Threads) dst[i] = src[i];
+    for (uint32_t i = 4 * n4 + threadIdx.x; i < n; i += kExact4Threads) rows[i] = v.bits[i];
     // and the row starts of G2 and of the incidence lists
     uint32_t* offs = rows + n;
-    for (uint32_t i = threadIdx.x; i <= v.N; i += kThreads) {
+    for (uint32_t i = threadIdx.x; i <= v.N; i += kExact4Threads) {
       offs[i] = v.g2_off[i];
       offs[v.N + 1 + i] = v.i3_off[i];
       offs[2 * (v.N + 1) + i] = v.i4_off[i];
@@ -137,9 +142,11 @@ __global__ void __launch_bounds__(kThreads) k_exact4_bits(ExactArgs a) {
     v.i4_off = offs + 2 * (v.N + 1);
   }
   load_lut(lut, a.lut, 2048);
-  h_main[threadIdx.x] = 0;
-  h_sub[threadIdx.x] = 0;
-  h_g2[threadIdx.x] = 0;
+  if (threadIdx.x < 256) {
+    h_main[threadIdx.x] = 0;
+    h_sub[threadIdx.x] = 0;
+    h_g2[threadIdx.x] = 0;
+  }
   __syncthreads();
   const int wv = threadIdx.x / kWave;
   const uint32_t lane = threadIdx.x & (kWave - 1);
@@ -149,8 +156,8 @@ __global__ void __launch_bounds__(kThreads) k_exact4_bits(ExactArgs a) {
   c4_zero(acc);
   const uint64_t n23 = a.n2 + a.n3;
   const uint64_t items = n23 + (a.n4 + kA4Chunk - 1) / kA4Chunk;
-  const uint64_t n_waves = uint64_t(gridDim.x) * kWavesPerBlock;
-  for (uint64_t i = uint64_t(blockIdx.x) * kWavesPerBlock + wv; i < items; i += n_waves) {
+  const uint64_t n_waves = uint64_t(gridDim.x) * kExact4Waves;
+  for (uint64_t i = uint64_t(blockIdx.x) * kExact4Waves + wv; i < items; i += n_waves) {
     if (i < a.n2) {
       c4_bits_item(v, v.e2[2 * i], v.e2[2 * i + 1], L, ylist[wv], acc, lut, h_g2);
     } else if (i < n23) {
@@ -208,7 +215,7 @@ constexpr unsigned kCountGrid = 512;
 
 // Workgroups of a fused counting launch: no more than are resident at once
 // (with `lds` bytes of dynamic LDS each), and no more than the items need.
-unsigned fused_grid(const void* kernel, size_t lds, uint64_t items, uint64_t per_block) {
+unsigned fused_grid(const void* kernel, size_t lds, uint64_t items, uint64_t per_block, int threads = kThreads) {
   struct Key {
     const void* kernel;
     size_t lds;
@@ -230,7 +237,7 @@ unsigned fused_grid(const void* kernel, size_t lds, uint64_t items, uint64_t per
   if (!resident) {
     int cus = 256, per_cu = 1;
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kThreads, lds) != hipSuccess || per_cu < 1)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, lds) != hipSuccess || per_cu < 1)
       per_cu = 1;
     resident = uint64_t(cus > 0 ? cus : 256) * uint64_t(per_cu);
     std::lock_guard<std::mutex> lock(mu);
@@ -281,16 +288,16 @@ int count_exact_impl(const hm_graph* H, int k, int64_t* counts, hipStream_t st) 
     if (k == 4) {
       const size_t rows = (size_t(v.N) * v.W + 3 * (size_t(v.N) + 1)) * 4;
       const bool lb = rows <= kLdsBitsMaxBytes;
-      const size_t lds = size_t(kWavesPerBlock) * b4_set_words(v.W) * 4 + (lb ? rows : 0);
+      const size_t lds = size_t(kExact4Waves) * b4_set_words(v.W) * 4 + (lb ? rows : 0);
       const uint64_t items = n2 + n3 + (n4 + kA4Chunk - 1) / kA4Chunk;
       const void* kern = lb ? reinterpret_cast<const void*>(k_exact4_bits<true>)
                             : reinterpret_cast<const void*>(k_exact4_bits<false>);
-      const unsigned grid = fused_grid(kern, lds, items, kWavesPerBlock);
+      const unsigned grid = fused_grid(kern, lds, items, kExact4Waves, kExact4Threads);
       ProfileScope ps("k_exact4_bits", st);
       if (lb)
-        k_exact4_bits<true><<<grid, kThreads, lds, st>>>(a);
+        k_exact4_bits<true><<<grid, kExact4Threads, lds, st>>>(a);
       else
-        k_exact4_bits<false><<<grid, kThreads, lds, st>>>(a);
+        k_exact4_bits<false><<<grid, kExact4Threads, lds, st>>>(a);
     } else {
       const unsigned grid = fused_grid(reinterpret_cast<const void*>(k_exact3_bits), 0, n2 * v.W + n3, kThreads);
       ProfileScope ps("k_exact3_bits", st);
