@@ -28,6 +28,8 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_exact_k4_facetoface_N
 # hardware counters is only reported while these are unchanged
 EXACT_SOURCES = ("exact.hip", "hm_items.h", "hm_b4.h", "hm_device.h", "hm_internal.h")
 HBM_PEAK_GBS = 8000.0
+# a hash probe into a table larger than the caches is one 64-byte transaction
+PROBE_BYTES = 64
 # integer VALU issue rate: 256 CUs x 64 lanes per cycle x 2.4 GHz
 ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 
@@ -55,6 +57,58 @@ def _unit_counts(e2: np.ndarray, e3: np.ndarray, n_nodes: int, words: int) -> di
         cand = int(deg2[t[:, 0]].sum() + deg2[t[:, 1]].sum() + deg2[t[:, 2]].sum()
                    + deg3[t[:, 0]].sum() + deg3[t[:, 1]].sum())
     return {"c4_word_tasks": int(ys) * words, "b4_word_tasks": int(len(e3)) * words, "b4_candidates": cand}
+
+
+def _b4_lookup_model(e2: np.ndarray, e3: np.ndarray, e4: np.ndarray, n_nodes: int) -> dict:
+    """Memory transactions of the 3-node-hyperedge fill-in step without bit
+    rows (one wavefront per 3-node hyperedge e = {a<b<c}), counted from the
+    strata.  Per e: 3 pair probes for e's own pattern, 3 pair-index lookups
+    and 1 codegree lookup; 2 pair probes per entry of the shortest pairwise
+    row among a, b, c; per other 3-node hyperedge {y} u P on a pair P of e,
+    with m the member of e outside P: 4 probes (two 3-node sets, one 4-node
+    set, one pair) when y > m, else 1, 2 or 3 (P = ab, ac, bc: the pair
+    {m, y} and the 3-node sets of the pairs before P); 6 probes (three
+    3-node sets, three pairs) per 4-node hyperedge holding e.  Streamed
+    bytes: 4 per row entry, 5 per pair-index entry (third node and its
+    adjacency), 20 per entry of the 4-node incidence list read, 60 for e and
+    its row bounds."""
+    n = np.int64(n_nodes)
+    if len(e3) == 0:
+        return {"probes": 0, "stream_bytes": 0, "hyperedges": 0}
+    deg2 = np.bincount(e2.reshape(-1).astype(np.int64), minlength=n_nodes) if len(e2) else np.zeros(n_nodes, np.int64)
+    t = e3.astype(np.int64)
+    a, b, c = t[:, 0], t[:, 1], t[:, 2]
+    dmin = np.minimum(np.minimum(deg2[a], deg2[b]), deg2[c])
+    # 3-node hyperedges on each pair, and how many of their third nodes lie
+    # below the member of e outside the pair
+    pk = np.concatenate([a * n + b, a * n + c, b * n + c])
+    third = np.concatenate([c, b, a])
+    uk, inv, cnt = np.unique(pk, return_inverse=True, return_counts=True)
+    runs3 = cnt[inv].reshape(3, -1)
+    runs = runs3.sum(axis=0)
+    by_third = np.sort(pk * n + third)
+    below = (np.searchsorted(by_third, pk * n + third) - np.searchsorted(by_third, pk * n)).reshape(3, -1)
+    others = runs3 - 1 - below
+    # 4-node hyperedges per node, and those holding each e
+    if len(e4):
+        q = e4.astype(np.int64)
+        deg4 = np.bincount(q.reshape(-1), minlength=n_nodes)
+        sub = np.concatenate([(q[:, i] * n + q[:, j]) * n + q[:, k]
+                              for i, j, k in ((0, 1, 2), (0, 1, 3), (0, 2, 3), (1, 2, 3))])
+        k3 = (a * n + b) * n + c
+        su, sc = np.unique(sub, return_counts=True)
+        pos = np.searchsorted(su, k3)
+        pos = np.minimum(pos, len(su) - 1)
+        holding = np.where(su[pos] == k3, sc[pos], 0)
+    else:
+        deg4 = np.zeros(n_nodes, np.int64)
+        holding = np.zeros(len(t), np.int64)
+    fa, fb, fc = deg4[a], deg4[b], deg4[c]
+    len3 = np.where((fa <= fb) & (fa <= fc), fa, np.where(fb <= fc, fb, fc))
+    probes = (7 * len(t) + 2 * dmin.sum() + 4 * others.sum() + (below * np.array([[1], [2], [3]])).sum()
+              + 6 * holding.sum())
+    stream = 4 * dmin.sum() + 5 * runs.sum() + 20 * len3.sum() + 60 * len(t)
+    return {"probes": int(probes), "stream_bytes": int(stream), "hyperedges": int(len(t))}
 
 
 def exact_source_digest() -> str:
@@ -116,6 +170,23 @@ def large_workloads(hm, W, torch, seeds: int = 32) -> dict:
         hm.count_exact(g, 4, stream=stream)
         exact_ms, res = timed(lambda i: hm.count_exact(g, 4, stream=stream), 3)
         exact = res[-1].cpu().numpy().astype(np.float64)
+        # the fill-in step of 3-node neighbourhoods, timed live with HIP events
+        # on the counting stream; effective lookup bandwidth at 64 B per probe
+        hm.hm_profile_reset()
+        hm.hm_profile_enable(True)
+        for _ in range(3):
+            hm.count_exact(g, 4, stream=stream)
+        torch.cuda.synchronize()
+        prof = hm.hm_profile_read()
+        hm.hm_profile_enable(False)
+        kernels = {k: {"launches": n, "avg_ms": ms / max(n, 1)} for k, (n, ms) in prof.items()}
+        model = _b4_lookup_model(g.export(2), g.export(3), g.export(4), h.n_nodes)
+        lookup = None
+        if "k_sp_b4" in kernels:
+            nbytes = model["probes"] * PROBE_BYTES + model["stream_bytes"]
+            gbs = nbytes / (kernels["k_sp_b4"]["avg_ms"] / 1e3) / 1e9
+            lookup = {"kernel": "k_sp_b4", "bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                      "frac": gbs / HBM_PEAK_GBS, "bytes_per_launch": nbytes, "probe_bytes": PROBE_BYTES, **model}
         h5 = W.subsample_edges(h, 0.05, seed=3)
         g5 = hm.hm_graph_create(h5.members, h5.offsets, h5.n_nodes, stream=stream)
         torch.cuda.synchronize()
@@ -153,6 +224,7 @@ def large_workloads(hm, W, torch, seeds: int = 32) -> dict:
             "first_call_ms": {"uniform_1pct_incl_index_build": first_uniform_ms,
                               "learned_1pct_incl_proposal": first_learned_ms},
             "learned_training_ms": train_ms, "training_set": "5% hyperedge subsample",
+            "exact_kernels": kernels, "lookup_roofline": lookup,
             "sampled": rows, "fastest_at_2pct_mre": {"uniform": best("uniform"), "learned": best("learned")},
             "seeds": seeds,
         }

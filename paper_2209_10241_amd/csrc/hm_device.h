@@ -103,6 +103,12 @@ __device__ inline uint32_t upper_bound(const uint32_t* adj, uint32_t p, uint32_t
   }
   return p;
 }
+// A value every active lane holds alike, moved to a scalar register.
+__device__ __forceinline__ uint32_t uniform_u32(uint32_t x) { return uint32_t(__builtin_amdgcn_readfirstlane(int(x))); }
+__device__ __forceinline__ uint64_t uniform_u64(uint64_t x) {
+  return (uint64_t(uniform_u32(uint32_t(x >> 32))) << 32) | uniform_u32(uint32_t(x));
+}
+
 // Wavefront sums with data-parallel-primitive moves (no LDS round trips):
 // shifts right by 1, 2, 4 and 8 lanes within each row of 16 leave a row's
 // total in its last lane; the broadcasts of lane 15 into rows 1 and 3 and of

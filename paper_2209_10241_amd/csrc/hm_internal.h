@@ -269,6 +269,9 @@ struct hm_graph {
   // adjacency to the pair's two nodes (bits 0 and 1)
   uint32_t* pl_third = nullptr;
   uint8_t* pl_adj = nullptr;
+  // the 3-node hyperedges by decreasing estimated cost of their exact
+  // neighbourhood count (built on first use without bit rows)
+  uint32_t* b4_order = nullptr;
   // per node, built on first use without bit rows: triangles at the node, sum
   // of its neighbours' degrees, its 3-node hyperedges by pairwise pattern (8)
   unsigned long long* ns_tri = nullptr;

@@ -124,6 +124,16 @@ __device__ __forceinline__ B4Ctx b4_ctx(const View& v, const PairLinks& pl, uint
   const uint32_t m4 = (fa <= fb && fa <= fc) ? a : (fb <= fc ? b : c);
   x.lo3 = v.i4_off[m4];
   x.len3 = v.i4_off[m4 + 1] - x.lo3;
+  // the same in every lane: kept in scalar registers
+  x.base_p = uniform_u32(x.base_p);
+  x.lo0 = uniform_u64(x.lo0);
+  x.lo1 = uniform_u64(x.lo1);
+  x.lo2 = uniform_u64(x.lo2);
+  x.lo3 = uniform_u64(x.lo3);
+  x.len0 = uniform_u64(x.len0);
+  x.len1 = uniform_u64(x.len1);
+  x.len2 = uniform_u64(x.len2);
+  x.len3 = uniform_u64(x.len3);
   x.total = x.len0 + x.len1 + x.len2 + x.len3;
   return x;
 }
@@ -209,6 +219,26 @@ __device__ __forceinline__ uint32_t b4_exception(const View& v, const PairLinks&
     y = pl.third[p];
     if (y == a || y == b || y == c) return 0;   // e itself
     pair_adj = pl.adj[p];
+    // The slot's own 3-node hyperedge {y} u pair comes after e only when y is
+    // above m, the member of e outside the pair (c, b, a for slots 0, 1, 2).
+    // Otherwise e is not the smallest 3-node hyperedge of e u {y}, so with
+    // OWN the set is not counted here: y only needs the earlier-slot test
+    // and its pair with m, for its pairwise combination.
+    const uint32_t m = slot == 0 ? c : (slot == 1 ? b : a);
+    if (OWN && y < m) {
+      Probe128 qab, qac;
+      if (slot >= 1) qab = probe3_start(v.hs3, a, b, y);
+      if (slot == 2) qac = probe3_start(v.hs3, a, c, y);
+      const Probe64 pm = probe2_start(v.hs2, m, y);
+      if (slot >= 1 && probe128_end(v.hs3, qab)) return 0;
+      if (slot == 2 && probe128_end(v.hs3, qac)) return 0;
+      const uint32_t mv = uint32_t(probe64_end(v.hs2, pm));
+      const uint32_t lo = pair_adj & 1u, hi = pair_adj >> 1;
+      const uint32_t av = slot == 2 ? mv : lo;
+      const uint32_t bv = slot == 0 ? hi : (slot == 1 ? mv : lo);
+      const uint32_t cv = slot == 0 ? mv : hi;
+      return 16u | av | (bv << 1) | (cv << 2);
+    }
   } else {
     const uint32_t* f = v.e4 + 4ull * v.i4_idx[p];
     const uint32_t f0 = f[0], f1 = f[1], f2 = f[2], f3 = f[3];

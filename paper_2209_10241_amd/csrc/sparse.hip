@@ -17,6 +17,8 @@
 // Degree order: x precedes y when (deg x, x) < (deg y, y); a node's
 // neighbours that follow it number at most sqrt(2 |E2|).
 #include <algorithm>
+#include <map>
+#include <mutex>
 #include <vector>
 
 #include "hm_sparse.h"
@@ -290,8 +292,12 @@ __global__ void k_es_widen(const uint32_t* __restrict__ t32, uint64_t n, unsigne
     t64[i] = t32[i];
 }
 
-// (b) at order 4 without bit rows: one wavefront per 3-node hyperedge.
-__global__ void __launch_bounds__(kThreads) k_sp_b4(View v, PairLinks pl, uint64_t n3, const uint8_t* __restrict__ lut_g,
+// (b) at order 4 without bit rows: one wavefront per 3-node hyperedge, taken
+// in the order `order` (decreasing estimated cost), so that the grid's
+// wavefronts, each taking every n_waves-th, get like shares of a
+// heavy-tailed workload.
+__global__ void __launch_bounds__(kThreads) k_sp_b4(View v, PairLinks pl, uint64_t n3, const uint32_t* __restrict__ order,
+                                                    const uint8_t* __restrict__ lut_g,
                                                     unsigned long long* __restrict__ hist) {
   __shared__ uint8_t lut[2048];
   __shared__ unsigned long long h_main[256], h_sub[256];
@@ -301,12 +307,36 @@ __global__ void __launch_bounds__(kThreads) k_sp_b4(View v, PairLinks pl, uint64
   __syncthreads();
   const uint64_t wave = uint64_t(blockIdx.x) * kWavesPerBlock + threadIdx.x / kWave;
   const uint64_t n_waves = uint64_t(gridDim.x) * kWavesPerBlock;
-  for (uint64_t i = wave; i < n3; i += n_waves)
+  for (uint64_t j = wave; j < n3; j += n_waves) {
+    const uint64_t i = order[j];
     b4_sparse<true>(v, pl, v.e3[3 * i], v.e3[3 * i + 1], v.e3[3 * i + 2], lut, h_main, h_sub);
+  }
   __syncthreads();
   unsigned long long* hc = hist_copy(hist, kExactHistStride);
   flush(h_main, hc + kMain, 256);
   flush(h_sub, hc + kSub, 256);
+}
+
+// Sort keys of the 3-node hyperedges for k_sp_b4: the complement of an
+// estimate of the memory transactions of each (two per entry of its shortest
+// pairwise row, four per 3-node hyperedge on one of its pairs, six per entry
+// of the 4-node incidence list it reads), with the hyperedge as value.
+__global__ void k_b4_cost_keys(View v, PairLinks pl, uint64_t n3, unsigned long long* __restrict__ keys,
+                               uint32_t* __restrict__ vals) {
+  for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n3; i += uint64_t(gridDim.x) * blockDim.x) {
+    const uint32_t a = v.e3[3 * i], b = v.e3[3 * i + 1], c = v.e3[3 * i + 2];
+    uint64_t lo;
+    uint32_t lab, lac, lbc;
+    pl_find(pl, ((unsigned long long)a << 32) | b, &lo, &lab);
+    pl_find(pl, ((unsigned long long)a << 32) | c, &lo, &lac);
+    pl_find(pl, ((unsigned long long)b << 32) | c, &lo, &lbc);
+    const uint64_t dmin = min(deg2_of(v, a), min(deg2_of(v, b), deg2_of(v, c)));
+    const uint32_t fa = v.i4_off[a + 1] - v.i4_off[a], fb = v.i4_off[b + 1] - v.i4_off[b],
+                   fc = v.i4_off[c + 1] - v.i4_off[c];
+    const uint64_t cost = 2 * dmin + 4 * (uint64_t(lab) + lac + lbc) + 6 * uint64_t(min(fa, min(fb, fc)));
+    keys[i] = 0xFFFFFFFFull - min<uint64_t>(cost, 0xFFFFFFFFull);
+    vals[i] = uint32_t(i);
+  }
 }
 
 // Induced shape counts from the non-induced ones, into the G2 region.
@@ -441,6 +471,24 @@ struct Scratch {
 unsigned grid_cap(uint64_t items, uint64_t per_block, unsigned cap) {
   uint64_t g = (items + per_block - 1) / per_block;
   return unsigned(std::max<uint64_t>(1, std::min<uint64_t>(g, cap)));
+}
+
+// Workgroups of kThreads threads (no dynamic LDS) of `kernel` resident on the
+// current device at once.
+unsigned resident_blocks(const void* kernel) {
+  static std::mutex mu;
+  static std::map<std::pair<const void*, int>, unsigned> cache;
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = cache.find({kernel, dev});
+  if (it != cache.end()) return it->second;
+  int cus = 256, per_cu = 1;
+  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kThreads, 0) != hipSuccess || per_cu < 1) per_cu = 1;
+  const unsigned r = unsigned(std::max(cus, 1)) * unsigned(per_cu);
+  cache[{kernel, dev}] = r;
+  return r;
 }
 
 }  // namespace
@@ -654,6 +702,37 @@ PairLinks pair_links_of(const hm_graph* H) {
   return pl;
 }
 
+// H->b4_order, after the pair index: the 3-node hyperedges sorted by
+// decreasing cost estimate.
+int ensure_b4_order(hm_graph* H, hipStream_t st) {
+  note_use(H, st);
+  const uint64_t n3 = H->n_by_size[3];
+  if (H->b4_order || n3 == 0) return HM_OK;
+  void *k = nullptr, *o = nullptr, *kt = nullptr, *ot = nullptr;
+  int rc = dalloc(&k, n3 * sizeof(unsigned long long));
+  if (rc == HM_OK) rc = dalloc(&o, n3 * sizeof(uint32_t));
+  if (rc == HM_OK) rc = dalloc(&kt, n3 * sizeof(unsigned long long));
+  if (rc == HM_OK) rc = dalloc(&ot, n3 * sizeof(uint32_t));
+  if (rc == HM_OK) {
+    k_b4_cost_keys<<<grid_cap(n3, 256, 4096), 256, 0, st>>>(view_of(H), pair_links_of(H), n3,
+                                                            static_cast<unsigned long long*>(k), static_cast<uint32_t*>(o));
+    if (hipGetLastError() != hipSuccess) rc = HM_EDEVICE;
+  }
+  if (rc == HM_OK)
+    rc = radix_sort_pairs(static_cast<unsigned long long*>(k), static_cast<uint32_t*>(o),
+                          static_cast<unsigned long long*>(kt), static_cast<uint32_t*>(ot), n3, 32, st);
+  if (rc == HM_OK && hipStreamSynchronize(st) != hipSuccess) rc = HM_EDEVICE;
+  dfree(k);
+  dfree(kt);
+  dfree(ot);
+  if (rc != HM_OK) {
+    dfree(o);
+    return rc;
+  }
+  H->b4_order = static_cast<uint32_t*>(o);
+  return HM_OK;
+}
+
 // Fills the main, sub and G2 regions of H->hist (zeroed by the caller) except
 // case (a), which the caller counts.
 int count_sparse(const hm_graph* H, int k, hipStream_t st) {
@@ -724,8 +803,12 @@ int count_sparse(const hm_graph* H, int k, hipStream_t st) {
   }
   if (k == 4 && n3) {
     HM_TRY(ensure_pair_links(const_cast<hm_graph*>(H), st));
+    HM_TRY(ensure_b4_order(const_cast<hm_graph*>(H), st));
+    // no more workgroups than are resident at once: each wavefront's share is
+    // fixed, and a workgroup that starts late would finish late
+    const unsigned grid = grid_cap(n3, kWavesPerBlock, resident_blocks(reinterpret_cast<const void*>(k_sp_b4)));
     ProfileScope ps("k_sp_b4", st);
-    k_sp_b4<<<grid_cap(n3, kWavesPerBlock, 2048), kThreads, 0, st>>>(v, pair_links_of(H), n3, lut4, H->hist);
+    k_sp_b4<<<grid, kThreads, 0, st>>>(v, pair_links_of(H), n3, H->b4_order, lut4, H->hist);
     HM_HIP(hipGetLastError());
   }
   k_sp_shapes<<<1, 64, 0, st>>>(acc, k, cls, H->hist);
