@@ -30,6 +30,11 @@ EXACT_SOURCES = ("exact.hip", "hm_items.h", "hm_b4.h", "hm_device.h", "hm_intern
 HBM_PEAK_GBS = 8000.0
 # a hash probe into a table larger than the caches is one 64-byte transaction
 PROBE_BYTES = 64
+# longest list of a 3-node hyperedge's neighbourhood that its fill-in step
+# holds in LDS and compares against instead of probing
+SHORT_RUN = 16
+# longest pairwise row of a member of that hyperedge it holds in LDS
+SHORT_ADJ = 64
 # integer VALU issue rate: 256 CUs x 64 lanes per cycle x 2.4 GHz
 ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 
@@ -64,14 +69,20 @@ def _b4_lookup_model(e2: np.ndarray, e3: np.ndarray, e4: np.ndarray, n_nodes: in
     rows (one wavefront per 3-node hyperedge e = {a<b<c}), counted from the
     strata.  Per e: 3 pair probes for e's own pattern, 3 pair-index lookups
     and 1 codegree lookup; 2 pair probes per entry of the shortest pairwise
-    row among a, b, c; per other 3-node hyperedge {y} u P on a pair P of e,
-    with m the member of e outside P: 4 probes (two 3-node sets, one 4-node
-    set, one pair) when y > m, else 1, 2 or 3 (P = ab, ac, bc: the pair
-    {m, y} and the 3-node sets of the pairs before P); 6 probes (three
-    3-node sets, three pairs) per 4-node hyperedge holding e.  Streamed
-    bytes: 4 per row entry, 5 per pair-index entry (third node and its
-    adjacency), 20 per entry of the 4-node incidence list read, 60 for e and
-    its row bounds."""
+    row among a, b, c.  Membership in the 3-node hyperedges through a pair
+    of e is a comparison when that pair's run has at most SHORT_RUN entries
+    (held in LDS), else a probe; membership in the 4-node hyperedges holding
+    e likewise when the 4-node incidence list read has at most 64 entries
+    and at most SHORT_RUN of them hold e.  Per other 3-node hyperedge
+    {y} u P on a pair P of e, with m the member of e outside P: when y > m,
+    the two other 3-node memberships, the 4-node membership and the pair
+    {m, y}; else the pair {m, y} and the 3-node memberships of the pairs
+    before P.  Per 4-node hyperedge holding e: its three 3-node memberships
+    and three pairs.  A pair with a member of e whose pairwise row has at
+    most SHORT_ADJ entries (held in LDS) is a comparison.  Streamed bytes: 4
+    per row entry, 5 per pair-index entry (third node and its adjacency), 20
+    per entry of the 4-node incidence list read, 60 for e and its row
+    bounds, and the short lists and rows read once more into LDS."""
     n = np.int64(n_nodes)
     if len(e3) == 0:
         return {"probes": 0, "stream_bytes": 0, "hyperedges": 0}
@@ -79,16 +90,16 @@ def _b4_lookup_model(e2: np.ndarray, e3: np.ndarray, e4: np.ndarray, n_nodes: in
     t = e3.astype(np.int64)
     a, b, c = t[:, 0], t[:, 1], t[:, 2]
     dmin = np.minimum(np.minimum(deg2[a], deg2[b]), deg2[c])
-    # 3-node hyperedges on each pair, and how many of their third nodes lie
-    # below the member of e outside the pair
+    # 3-node hyperedges on each pair (ab, ac, bc), and how many of their
+    # third nodes lie below the member of e outside the pair
     pk = np.concatenate([a * n + b, a * n + c, b * n + c])
     third = np.concatenate([c, b, a])
     uk, inv, cnt = np.unique(pk, return_inverse=True, return_counts=True)
-    runs3 = cnt[inv].reshape(3, -1)
-    runs = runs3.sum(axis=0)
+    L = cnt[inv].reshape(3, -1)
     by_third = np.sort(pk * n + third)
     below = (np.searchsorted(by_third, pk * n + third) - np.searchsorted(by_third, pk * n)).reshape(3, -1)
-    others = runs3 - 1 - below
+    late = L - 1 - below
+    probed = (L > SHORT_RUN).astype(np.int64)   # membership through that pair is a probe
     # 4-node hyperedges per node, and those holding each e
     if len(e4):
         q = e4.astype(np.int64)
@@ -97,17 +108,26 @@ def _b4_lookup_model(e2: np.ndarray, e3: np.ndarray, e4: np.ndarray, n_nodes: in
                               for i, j, k in ((0, 1, 2), (0, 1, 3), (0, 2, 3), (1, 2, 3))])
         k3 = (a * n + b) * n + c
         su, sc = np.unique(sub, return_counts=True)
-        pos = np.searchsorted(su, k3)
-        pos = np.minimum(pos, len(su) - 1)
+        pos = np.minimum(np.searchsorted(su, k3), len(su) - 1)
         holding = np.where(su[pos] == k3, sc[pos], 0)
     else:
         deg4 = np.zeros(n_nodes, np.int64)
         holding = np.zeros(len(t), np.int64)
     fa, fb, fc = deg4[a], deg4[b], deg4[c]
     len3 = np.where((fa <= fb) & (fa <= fc), fa, np.where(fb <= fc, fb, fc))
-    probes = (7 * len(t) + 2 * dmin.sum() + 4 * others.sum() + (below * np.array([[1], [2], [3]])).sum()
-              + 6 * holding.sum())
-    stream = 4 * dmin.sum() + 5 * runs.sum() + 20 * len3.sum() + 60 * len(t)
+    q_held = (len3 <= 64) & (holding <= SHORT_RUN)
+    qp = (~q_held).astype(np.int64)
+    ab, ac, bc = probed
+    # pairs with a member of e are comparisons when its pairwise row is held
+    da, db, dc = deg2[a], deg2[b], deg2[c]
+    pa, pb, pc = ((d > SHORT_ADJ).astype(np.int64) for d in (da, db, dc))
+    probes = (7 + 2 * dmin
+              + late[0] * (ac + bc + qp + pc) + late[1] * (ab + bc + qp + pb) + late[2] * (ab + ac + qp + pa)
+              + below[0] * pc + below[1] * (ab + pb) + below[2] * (ab + ac + pa)
+              + holding * (ab + ac + bc + pa + pb + pc)).sum()
+    held_rows = sum(np.where(d <= SHORT_ADJ, d, 0) for d in (da, db, dc))
+    stream = (4 * dmin + 5 * L.sum(axis=0) + 20 * len3 + 60
+              + 4 * (L * (1 - probed)).sum(axis=0) + 20 * np.where(len3 <= 64, len3, 0) + 4 * held_rows).sum()
     return {"probes": int(probes), "stream_bytes": int(stream), "hyperedges": int(len(t))}
 
 

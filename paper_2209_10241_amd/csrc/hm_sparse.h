@@ -189,15 +189,97 @@ __device__ __forceinline__ void b4_combo_counts(const View& v, const PairLinks& 
   n[4] = sc - n[5] - n[6] - n[7];
 }
 
+// Short lists of e's neighbourhood in a wavefront's LDS, so that a membership
+// test is a comparison rather than a hash probe: the third nodes of the run
+// of each pair of e when it has at most kB4ShortRun entries, the fourth
+// nodes of the 4-node hyperedges holding e (at most kB4ShortRun of them,
+// found in a 4-node incidence list of at most kWave entries), and the
+// pairwise neighbours of each member of e with at most kB4ShortAdj of them.
+// Lists are padded with kNoNode to a multiple of 4; a count of kB4NotHeld
+// means the list is not held and membership is probed.
+constexpr uint32_t kB4ShortRun = 16;
+constexpr uint32_t kB4ShortAdj = kWave;
+constexpr uint32_t kB4NotHeld = 0xFFFFFFFFu;
+constexpr uint32_t kNoNode = 0xFFFFFFFFu;
+constexpr uint32_t kB4AdjAt = 4 * kB4ShortRun;                    // after ab, ac, bc, the 4-node list
+constexpr uint32_t kB4ShortWords = kB4AdjAt + 3 * kB4ShortAdj;   // per wavefront
+
+struct B4Short {
+  const uint32_t* mem;   // 16-byte aligned, kB4ShortWords words
+  uint32_t n_ab, n_ac, n_bc, n_q;
+  uint32_t n_a, n_b, n_c;   // pairwise neighbours of a, b, c
+};
+
+__device__ __forceinline__ bool in_short(const uint32_t* l, uint32_t n, uint32_t y) {
+  bool r = false;
+  for (uint32_t k = 0; k < n; k += 4) {
+    const uint4 q = *reinterpret_cast<const uint4*>(l + k);
+    r |= (q.x == y) | (q.y == y) | (q.z == y) | (q.w == y);
+  }
+  return r;
+}
+
+// Every lane of the wavefront calls this; mem is the wavefront's LDS.
+__device__ __forceinline__ B4Short b4_short(const View& v, const PairLinks& pl, const B4Ctx& x, uint32_t* mem) {
+  const uint32_t lane = threadIdx.x & (kWave - 1);
+  const unsigned long long below = (1ull << lane) - 1ull;
+  B4Short s;
+  s.mem = mem;
+  s.n_ab = x.len0 <= kB4ShortRun ? uint32_t(x.len0) : kB4NotHeld;
+  s.n_ac = x.len1 <= kB4ShortRun ? uint32_t(x.len1) : kB4NotHeld;
+  s.n_bc = x.len2 <= kB4ShortRun ? uint32_t(x.len2) : kB4NotHeld;
+  if (lane < kB4ShortRun) {
+    if (s.n_ab != kB4NotHeld) mem[lane] = lane < x.len0 ? pl.third[x.lo0 + lane] : kNoNode;
+    if (s.n_ac != kB4NotHeld) mem[kB4ShortRun + lane] = lane < x.len1 ? pl.third[x.lo1 + lane] : kNoNode;
+    if (s.n_bc != kB4NotHeld) mem[2 * kB4ShortRun + lane] = lane < x.len2 ? pl.third[x.lo2 + lane] : kNoNode;
+  }
+  const uint32_t da = deg2_of(v, x.a), db = deg2_of(v, x.b), dc = deg2_of(v, x.c);
+  s.n_a = da <= kB4ShortAdj ? da : kB4NotHeld;
+  s.n_b = db <= kB4ShortAdj ? db : kB4NotHeld;
+  s.n_c = dc <= kB4ShortAdj ? dc : kB4NotHeld;
+  if (lane < kB4ShortAdj) {
+    if (s.n_a != kB4NotHeld) mem[kB4AdjAt + lane] = lane < da ? v.g2_adj[v.g2_off[x.a] + lane] : kNoNode;
+    if (s.n_b != kB4NotHeld) mem[kB4AdjAt + kB4ShortAdj + lane] = lane < db ? v.g2_adj[v.g2_off[x.b] + lane] : kNoNode;
+    if (s.n_c != kB4NotHeld) mem[kB4AdjAt + 2 * kB4ShortAdj + lane] = lane < dc ? v.g2_adj[v.g2_off[x.c] + lane] : kNoNode;
+  }
+  s.n_q = kB4NotHeld;
+  if (x.len3 <= kWave) {
+    bool hold = false;
+    uint32_t y = 0;
+    if (lane < x.len3) {
+      const uint32_t* f = v.e4 + 4ull * v.i4_idx[x.lo3 + lane];
+      const uint32_t f0 = f[0], f1 = f[1], f2 = f[2], f3 = f[3];
+      const uint32_t hit = uint32_t(f0 == x.a || f0 == x.b || f0 == x.c) + uint32_t(f1 == x.a || f1 == x.b || f1 == x.c) +
+                           uint32_t(f2 == x.a || f2 == x.b || f2 == x.c) + uint32_t(f3 == x.a || f3 == x.b || f3 == x.c);
+      hold = hit == 3;
+      y = f0 ^ f1 ^ f2 ^ f3 ^ x.a ^ x.b ^ x.c;
+    }
+    const unsigned long long m = __ballot(hold);
+    const uint32_t nq = uint32_t(__popcll(m));
+    if (nq <= kB4ShortRun) {
+      if (lane < kB4ShortRun) mem[3 * kB4ShortRun + lane] = kNoNode;
+      wave_sync();
+      if (hold) mem[3 * kB4ShortRun + uint32_t(__popcll(m & below))] = y;
+      s.n_q = nq;
+    }
+  }
+  wave_sync();
+  return s;
+}
+
 // The exceptional node at flat position t of the ranges of x, each node
 // once (by the first hyperedge that makes it exceptional).  Returns 0 when the
 // position holds none; else bit 4 set, its pairwise combination in bits 0..2,
 // bit 3 set when its set counts (not a 4-node hyperedge and, with OWN, e its
-// smallest 3-node hyperedge), with the set's pattern in *pat.
+// smallest 3-node hyperedge), with the set's pattern in *pat.  With sh, the
+// lists it holds replace the corresponding probes.
 template <bool OWN>
 __device__ __forceinline__ uint32_t b4_exception(const View& v, const PairLinks& pl, const B4Ctx& x, uint64_t t,
-                                        uint32_t* pat) {
+                                        uint32_t* pat, const B4Short* sh = nullptr) {
   const uint32_t a = x.a, b = x.b, c = x.c;
+  const bool hab = sh && sh->n_ab != kB4NotHeld, hac = sh && sh->n_ac != kB4NotHeld,
+             hbc = sh && sh->n_bc != kB4NotHeld, hq = sh && sh->n_q != kB4NotHeld;
+  const bool ha = sh && sh->n_a != kB4NotHeld, hb = sh && sh->n_b != kB4NotHeld, hc = sh && sh->n_c != kB4NotHeld;
   // slot and offset of t, with constant indices only (registers)
   int slot;
   uint64_t p;
@@ -227,12 +309,18 @@ __device__ __forceinline__ uint32_t b4_exception(const View& v, const PairLinks&
     const uint32_t m = slot == 0 ? c : (slot == 1 ? b : a);
     if (OWN && y < m) {
       Probe128 qab, qac;
-      if (slot >= 1) qab = probe3_start(v.hs3, a, b, y);
-      if (slot == 2) qac = probe3_start(v.hs3, a, c, y);
-      const Probe64 pm = probe2_start(v.hs2, m, y);
-      if (slot >= 1 && probe128_end(v.hs3, qab)) return 0;
-      if (slot == 2 && probe128_end(v.hs3, qac)) return 0;
-      const uint32_t mv = uint32_t(probe64_end(v.hs2, pm));
+      if (slot >= 1 && !hab) qab = probe3_start(v.hs3, a, b, y);
+      if (slot == 2 && !hac) qac = probe3_start(v.hs3, a, c, y);
+      // m's neighbours, when held: c's for slot 0, b's for slot 1, a's for slot 2
+      const bool hm = slot == 0 ? hc : (slot == 1 ? hb : ha);
+      Probe64 pm;
+      if (!hm) pm = probe2_start(v.hs2, m, y);
+      if (slot >= 1 && (hab ? in_short(sh->mem, sh->n_ab, y) : probe128_end(v.hs3, qab))) return 0;
+      if (slot == 2 && (hac ? in_short(sh->mem + kB4ShortRun, sh->n_ac, y) : probe128_end(v.hs3, qac))) return 0;
+      const uint32_t mv =
+          hm ? uint32_t(in_short(sh->mem + kB4AdjAt + (2 - uint32_t(slot)) * kB4ShortAdj,
+                                 slot == 0 ? sh->n_c : (slot == 1 ? sh->n_b : sh->n_a), y))
+             : uint32_t(probe64_end(v.hs2, pm));
       const uint32_t lo = pair_adj & 1u, hi = pair_adj >> 1;
       const uint32_t av = slot == 2 ? mv : lo;
       const uint32_t bv = slot == 0 ? hi : (slot == 1 ? mv : lo);
@@ -251,10 +339,10 @@ __device__ __forceinline__ uint32_t b4_exception(const View& v, const PairLinks&
   // 3-node sets through y not already known from the slot, the 4-node set
   // (unless the slot is the 4-node hyperedges'), y's pairs with a, b, c.
   Probe128 pab, pac, pbc, pq;
-  if (slot != 0) pab = probe3_start(v.hs3, a, b, y);
-  if (slot != 1) pac = probe3_start(v.hs3, a, c, y);
-  if (slot != 2) pbc = probe3_start(v.hs3, b, c, y);
-  if (slot < 3) {
+  if (slot != 0 && !hab) pab = probe3_start(v.hs3, a, b, y);
+  if (slot != 1 && !hac) pac = probe3_start(v.hs3, a, c, y);
+  if (slot != 2 && !hbc) pbc = probe3_start(v.hs3, b, c, y);
+  if (slot < 3 && !hq) {
     uint32_t s0 = a, s1 = b, s2 = c, s3 = y;
     // ascending 4-tuple for the 4-node probe
     if (s3 < s2) { const uint32_t tt = s2; s2 = s3; s3 = tt; }
@@ -264,20 +352,33 @@ __device__ __forceinline__ uint32_t b4_exception(const View& v, const PairLinks&
   }
   // y's pairs with the two members of the slot's pair come with the entry
   Probe64 pa, pb, pc;
-  if (slot == 2 || slot == 3) pa = probe2_start(v.hs2, a, y);
-  if (slot == 1 || slot == 3) pb = probe2_start(v.hs2, b, y);
-  if (slot == 0 || slot == 3) pc = probe2_start(v.hs2, c, y);
-  const uint32_t abv = slot == 0 ? 1u : uint32_t(probe128_end(v.hs3, pab));
-  const uint32_t acv = slot == 1 ? 1u : uint32_t(probe128_end(v.hs3, pac));
-  const uint32_t bcv = slot == 2 ? 1u : uint32_t(probe128_end(v.hs3, pbc));
+  if ((slot == 2 || slot == 3) && !ha) pa = probe2_start(v.hs2, a, y);
+  if ((slot == 1 || slot == 3) && !hb) pb = probe2_start(v.hs2, b, y);
+  if ((slot == 0 || slot == 3) && !hc) pc = probe2_start(v.hs2, c, y);
+  const uint32_t abv =
+      slot == 0 ? 1u : uint32_t(hab ? in_short(sh->mem, sh->n_ab, y) : probe128_end(v.hs3, pab));
+  const uint32_t acv =
+      slot == 1 ? 1u : uint32_t(hac ? in_short(sh->mem + kB4ShortRun, sh->n_ac, y) : probe128_end(v.hs3, pac));
+  const uint32_t bcv =
+      slot == 2 ? 1u : uint32_t(hbc ? in_short(sh->mem + 2 * kB4ShortRun, sh->n_bc, y) : probe128_end(v.hs3, pbc));
   // each exceptional node once: a 3-node hyperedge of an earlier slot takes it
   if (slot == 1 && abv) return 0;
   if (slot == 2 && (abv || acv)) return 0;
   if (slot == 3 && (abv || acv || bcv)) return 0;
-  const uint32_t quad = slot == 3 ? 1u : uint32_t(probe128_end(v.hs4, pq));
-  const uint32_t av = slot == 0 || slot == 1 ? (pair_adj & 1u) : uint32_t(probe64_end(v.hs2, pa));
-  const uint32_t bv = slot == 0 ? (pair_adj >> 1) : (slot == 2 ? (pair_adj & 1u) : uint32_t(probe64_end(v.hs2, pb)));
-  const uint32_t cv = slot == 1 || slot == 2 ? (pair_adj >> 1) : uint32_t(probe64_end(v.hs2, pc));
+  const uint32_t quad =
+      slot == 3 ? 1u : uint32_t(hq ? in_short(sh->mem + 3 * kB4ShortRun, sh->n_q, y) : probe128_end(v.hs4, pq));
+  const uint32_t av = slot == 0 || slot == 1
+                          ? (pair_adj & 1u)
+                          : uint32_t(ha ? in_short(sh->mem + kB4AdjAt, sh->n_a, y) : probe64_end(v.hs2, pa));
+  const uint32_t bv =
+      slot == 0 ? (pair_adj >> 1)
+                : (slot == 2 ? (pair_adj & 1u)
+                             : uint32_t(hb ? in_short(sh->mem + kB4AdjAt + kB4ShortAdj, sh->n_b, y)
+                                           : probe64_end(v.hs2, pb)));
+  const uint32_t cv = slot == 1 || slot == 2
+                          ? (pair_adj >> 1)
+                          : uint32_t(hc ? in_short(sh->mem + kB4AdjAt + 2 * kB4ShortAdj, sh->n_c, y)
+                                        : probe64_end(v.hs2, pc));
   const uint32_t combo = av | (bv << 1) | (cv << 2);
   bool counted = !quad;   // a 4-node hyperedge: counted on its own, or larger than a sampled 3-node one
   if (OWN && counted) {
@@ -302,17 +403,19 @@ __device__ inline uint32_t b4_combo_pattern(const B4Ctx& x, uint32_t cmb) {
 // wavefront per hyperedge.
 template <bool OWN>
 __device__ void b4_sparse(const View& v, const PairLinks& pl, uint32_t a, uint32_t b, uint32_t c, const uint8_t* lut,
-                          unsigned long long* h_main, unsigned long long* h_sub) {
+                          unsigned long long* h_main, unsigned long long* h_sub, uint32_t* short_mem = nullptr) {
   const int lane = threadIdx.x & (kWave - 1);
   const B4Ctx x = b4_ctx(v, pl, a, b, c);
   uint32_t n[8];
   b4_combo_counts(v, pl, x, n);
+  B4Short sh;
+  if (short_mem) sh = b4_short(v, pl, x, short_mem);
   // exceptional nodes, in one lane-strided range; per lane, the number of
   // them in each pairwise combination
   uint32_t dn1 = 0, dn2 = 0, dn3 = 0, dn4 = 0, dn5 = 0, dn6 = 0, dn7 = 0;
   for (uint64_t t = lane; t < x.total; t += kWave) {
     uint32_t pat;
-    const uint32_t r = b4_exception<OWN>(v, pl, x, t, &pat);
+    const uint32_t r = b4_exception<OWN>(v, pl, x, t, &pat, short_mem ? &sh : nullptr);
     if (!r) continue;
     const uint32_t combo = r & 7u;
     dn1 += combo == 1;

@@ -301,15 +301,17 @@ __global__ void __launch_bounds__(kThreads) k_sp_b4(View v, PairLinks pl, uint64
                                                     unsigned long long* __restrict__ hist) {
   __shared__ uint8_t lut[2048];
   __shared__ unsigned long long h_main[256], h_sub[256];
+  __shared__ __align__(16) uint32_t short_lists[kWavesPerBlock][kB4ShortWords];
   load_lut(lut, lut_g, 2048);
   h_main[threadIdx.x] = 0;
   h_sub[threadIdx.x] = 0;
   __syncthreads();
   const uint64_t wave = uint64_t(blockIdx.x) * kWavesPerBlock + threadIdx.x / kWave;
   const uint64_t n_waves = uint64_t(gridDim.x) * kWavesPerBlock;
+  uint32_t* short_mem = short_lists[threadIdx.x / kWave];
   for (uint64_t j = wave; j < n3; j += n_waves) {
     const uint64_t i = order[j];
-    b4_sparse<true>(v, pl, v.e3[3 * i], v.e3[3 * i + 1], v.e3[3 * i + 2], lut, h_main, h_sub);
+    b4_sparse<true>(v, pl, v.e3[3 * i], v.e3[3 * i + 1], v.e3[3 * i + 2], lut, h_main, h_sub, short_mem);
   }
   __syncthreads();
   unsigned long long* hc = hist_copy(hist, kExactHistStride);
