@@ -32,7 +32,8 @@ HBM_PEAK_GBS = 8000.0
 PROBE_BYTES = 64
 # longest list of a 3-node hyperedge's neighbourhood that its fill-in step
 # holds in LDS and compares against instead of probing
-SHORT_RUN = 16
+SHORT_RUN = 64
+SHORT_Q = 16
 # longest pairwise row of a member of that hyperedge it holds in LDS
 SHORT_ADJ = 64
 # integer VALU issue rate: 256 CUs x 64 lanes per cycle x 2.4 GHz
@@ -73,7 +74,7 @@ def _b4_lookup_model(e2: np.ndarray, e3: np.ndarray, e4: np.ndarray, n_nodes: in
     of e is a comparison when that pair's run has at most SHORT_RUN entries
     (held in LDS), else a probe; membership in the 4-node hyperedges holding
     e likewise when the 4-node incidence list read has at most 64 entries
-    and at most SHORT_RUN of them hold e.  Per other 3-node hyperedge
+    and at most SHORT_Q of them hold e.  Per other 3-node hyperedge
     {y} u P on a pair P of e, with m the member of e outside P: when y > m,
     the two other 3-node memberships, the 4-node membership and the pair
     {m, y}; else the pair {m, y} and the 3-node memberships of the pairs
@@ -115,7 +116,7 @@ def _b4_lookup_model(e2: np.ndarray, e3: np.ndarray, e4: np.ndarray, n_nodes: in
         holding = np.zeros(len(t), np.int64)
     fa, fb, fc = deg4[a], deg4[b], deg4[c]
     len3 = np.where((fa <= fb) & (fa <= fc), fa, np.where(fb <= fc, fb, fc))
-    q_held = (len3 <= 64) & (holding <= SHORT_RUN)
+    q_held = (len3 <= 64) & (holding <= SHORT_Q)
     qp = (~q_held).astype(np.int64)
     ab, ac, bc = probed
     # pairs with a member of e are comparisons when its pairwise row is held

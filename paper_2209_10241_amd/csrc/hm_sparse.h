@@ -192,16 +192,18 @@ __device__ __forceinline__ void b4_combo_counts(const View& v, const PairLinks& 
 // Short lists of e's neighbourhood in a wavefront's LDS, so that a membership
 // test is a comparison rather than a hash probe: the third nodes of the run
 // of each pair of e when it has at most kB4ShortRun entries, the fourth
-// nodes of the 4-node hyperedges holding e (at most kB4ShortRun of them,
+// nodes of the 4-node hyperedges holding e (at most kB4ShortQ of them,
 // found in a 4-node incidence list of at most kWave entries), and the
 // pairwise neighbours of each member of e with at most kB4ShortAdj of them.
 // Lists are padded with kNoNode to a multiple of 4; a count of kB4NotHeld
 // means the list is not held and membership is probed.
-constexpr uint32_t kB4ShortRun = 16;
+constexpr uint32_t kB4ShortRun = kWave;
+constexpr uint32_t kB4ShortQ = 16;
 constexpr uint32_t kB4ShortAdj = kWave;
 constexpr uint32_t kB4NotHeld = 0xFFFFFFFFu;
 constexpr uint32_t kNoNode = 0xFFFFFFFFu;
-constexpr uint32_t kB4AdjAt = 4 * kB4ShortRun;                    // after ab, ac, bc, the 4-node list
+constexpr uint32_t kB4QAt = 3 * kB4ShortRun;                      // after ab, ac, bc
+constexpr uint32_t kB4AdjAt = kB4QAt + kB4ShortQ;                 // after the 4-node list
 constexpr uint32_t kB4ShortWords = kB4AdjAt + 3 * kB4ShortAdj;   // per wavefront
 
 struct B4Short {
@@ -256,10 +258,10 @@ __device__ __forceinline__ B4Short b4_short(const View& v, const PairLinks& pl, 
     }
     const unsigned long long m = __ballot(hold);
     const uint32_t nq = uint32_t(__popcll(m));
-    if (nq <= kB4ShortRun) {
-      if (lane < kB4ShortRun) mem[3 * kB4ShortRun + lane] = kNoNode;
+    if (nq <= kB4ShortQ) {
+      if (lane < kB4ShortQ) mem[kB4QAt + lane] = kNoNode;
       wave_sync();
-      if (hold) mem[3 * kB4ShortRun + uint32_t(__popcll(m & below))] = y;
+      if (hold) mem[kB4QAt + uint32_t(__popcll(m & below))] = y;
       s.n_q = nq;
     }
   }
@@ -366,7 +368,7 @@ __device__ __forceinline__ uint32_t b4_exception(const View& v, const PairLinks&
   if (slot == 2 && (abv || acv)) return 0;
   if (slot == 3 && (abv || acv || bcv)) return 0;
   const uint32_t quad =
-      slot == 3 ? 1u : uint32_t(hq ? in_short(sh->mem + 3 * kB4ShortRun, sh->n_q, y) : probe128_end(v.hs4, pq));
+      slot == 3 ? 1u : uint32_t(hq ? in_short(sh->mem + kB4QAt, sh->n_q, y) : probe128_end(v.hs4, pq));
   const uint32_t av = slot == 0 || slot == 1
                           ? (pair_adj & 1u)
                           : uint32_t(ha ? in_short(sh->mem + kB4AdjAt, sh->n_a, y) : probe64_end(v.hs2, pa));
