@@ -91,8 +91,8 @@ enum : uint32_t { kJobNone = 0, kJobPairT = 1, kJobPairR = 2, kJobTriple = 3, kJ
 // default chunk sizes (divided by the HM_OPT_SAMPLE_CHUNK_SCALE option)
 constexpr uint32_t kChunkT = 4;    // nodes of T per chunk
 constexpr uint32_t kChunkR = 16;   // correction items per chunk
-constexpr uint32_t kChunkX = 32;   // exception positions per chunk
-constexpr uint32_t kChunkH = 64;   // hyperedges at s (3-node) or holding e (4-node) per chunk
+constexpr uint32_t kChunkX = 128;  // exception positions per chunk
+constexpr uint32_t kChunkH = 256;  // hyperedges at s (3-node) or holding e (4-node) per chunk
 // queue entries per sample of strata 2 and 3 (times the chunk option), at
 // most kQueueMax in all; work that finds the queue full is done in place
 constexpr uint64_t kQueuePerSample = 512;
