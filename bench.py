@@ -86,7 +86,7 @@ def _b4_lookup_model(e2: np.ndarray, e3: np.ndarray, e4: np.ndarray, n_nodes: in
     bounds, and the short lists and rows read once more into LDS."""
     n = np.int64(n_nodes)
     if len(e3) == 0:
-        return {"probes": 0, "stream_bytes": 0, "hyperedges": 0}
+        return {"probes": 0, "stream_bytes": 0, "hyperedges": 0, "entries": 0}
     deg2 = np.bincount(e2.reshape(-1).astype(np.int64), minlength=n_nodes) if len(e2) else np.zeros(n_nodes, np.int64)
     t = e3.astype(np.int64)
     a, b, c = t[:, 0], t[:, 1], t[:, 2]
@@ -129,7 +129,10 @@ def _b4_lookup_model(e2: np.ndarray, e3: np.ndarray, e4: np.ndarray, n_nodes: in
     held_rows = sum(np.where(d <= SHORT_ADJ, d, 0) for d in (da, db, dc))
     stream = (4 * dmin + 5 * L.sum(axis=0) + 20 * len3 + 60
               + 4 * (L * (1 - probed)).sum(axis=0) + 20 * np.where(len3 <= 64, len3, 0) + 4 * held_rows).sum()
-    return {"probes": int(probes), "stream_bytes": int(stream), "hyperedges": int(len(t))}
+    # positions the exception loops walk: every entry of the three pair runs
+    # and of the 4-node incidence list read
+    entries = int(L.sum() + len3.sum())
+    return {"probes": int(probes), "stream_bytes": int(stream), "hyperedges": int(len(t)), "entries": entries}
 
 
 def exact_source_digest() -> str:
@@ -154,7 +157,7 @@ def measured_traffic() -> dict:
     for l in lines:
         cols = [c.strip() for c in l.strip().strip("|").split("|")]
         if len(cols) == 6 and cols[0].startswith("k_") and cols[5].replace(".", "").isdigit():
-            out[cols[0]] = float(cols[5])
+            out[cols[0].split("<")[0]] = float(cols[5])
     return out
 
 
@@ -163,9 +166,10 @@ def _mre(runs, exact) -> float:
     return float(np.mean(np.abs(r - exact).sum(axis=1) / exact.sum()))
 
 
-def large_workloads(hm, W, torch, seeds: int = 32) -> dict:
+def large_workloads(hm, W, torch, seeds: int = 32, exact_only: bool = False) -> dict:
     """Exact order-4 counts and sampled estimates (uniform, and the learned
-    proposal trained on a 5% hyperedge subsample) on the heavy-tailed workloads."""
+    proposal trained on a 5% hyperedge subsample) on the heavy-tailed
+    workloads; with exact_only, the exact counts and their lookup figures."""
     out = {}
     stream = torch.cuda.current_stream()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -207,7 +211,16 @@ def large_workloads(hm, W, torch, seeds: int = 32) -> dict:
             nbytes = model["probes"] * PROBE_BYTES + model["stream_bytes"]
             gbs = nbytes / (kernels["k_sp_b4"]["avg_ms"] / 1e3) / 1e9
             lookup = {"kernel": "k_sp_b4", "bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                      "frac": gbs / HBM_PEAK_GBS, "bytes_per_launch": nbytes, "probe_bytes": PROBE_BYTES, **model}
+                      "frac": gbs / HBM_PEAK_GBS, "bytes_per_launch": nbytes, "probe_bytes": PROBE_BYTES,
+                      "entries_per_s": model["entries"] / (kernels["k_sp_b4"]["avg_ms"] / 1e3), **model}
+        if exact_only:
+            out[name] = {"n_nodes": h.n_nodes, "unique_by_size": [st["n2"], st["n3"], st["n4"], st["n5plus"]],
+                         "connected_4_sets": int(exact.sum()), "ingest_ms": ingest_ms, "exact_ms": exact_ms,
+                         "exact_kernels": kernels, "lookup_roofline": lookup}
+            g.close()
+            del members, offsets
+            torch.cuda.empty_cache()
+            continue
         h5 = W.subsample_edges(h, 0.05, seed=3)
         g5 = hm.hm_graph_create(h5.members, h5.offsets, h5.n_nodes, stream=stream)
         torch.cuda.synchronize()
@@ -266,6 +279,9 @@ def main() -> int:
     ap.add_argument("--exact-only", action="store_true", help="skip the sampled and null-model measurements")
     ap.add_argument("--no-large", action="store_true",
                     help="skip the co-authorship and communication workloads (exact, uniform and learned sampling)")
+    ap.add_argument("--lookup-only", action="store_true",
+                    help="only the exact counts of the co-authorship and communication workloads and their "
+                         "lookup-bandwidth figures (one JSON line)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first copy 256 MiB device to device (a kernel of known traffic for counter scaling)")
     args = ap.parse_args()
@@ -286,6 +302,9 @@ def main() -> int:
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if args.lookup_only:
+        print(json.dumps({"large_workloads": large_workloads(hm, W, torch, exact_only=True)}))
+        return 0
     h = W.cfg1_facetoface_k4(0)
     members = torch.from_numpy(h.members.astype(np.int32)).to(dev)
     offsets = torch.from_numpy(h.offsets.astype(np.int64)).to(dev)
