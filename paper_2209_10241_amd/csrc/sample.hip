@@ -319,6 +319,17 @@ __device__ inline uint32_t j2_cls(const View& v, const J2Ctx& c, uint32_t y) {
 __device__ inline uint32_t j2_t_node(const View& v, const PairLinks& pl, const J2Ctx& c, uint64_t p) {
   return pl.third[p];
 }
+// j2_cls of the node of T at index entry p, from the entry's adjacency bits
+// (bit 0: e0 ~ t, bit 1: e1 ~ t, with e0 < e1 the sampled pair)
+__device__ inline uint32_t j2_t_cls(const PairLinks& pl, const J2Ctx& c, uint64_t p) {
+  const uint32_t adj = pl.adj[p];
+  return c.s == c.e0 ? adj : (((adj & 1u) << 1) | (adj >> 1));
+}
+// j2_agg_pat(v, c, s, t) for t in T with class cls: o ~ s holds (e is a pair)
+__device__ inline uint32_t j2_agg_pat_t(const J2Ctx& c, uint32_t t, uint32_t cls) {
+  const uint32_t st = cls & 1u, ot = cls >> 1;
+  return c.s < t ? (1u | (1u << 2) | (ot << 5) | (st << 7)) : (1u | (ot << 2) | (1u << 5) | (st << 7));
+}
 // a pair {x, y} outside X whose set holds a larger hyperedge, taken off
 __device__ inline void j2_remove(const View& v, const J2Ctx& c, const uint8_t* lut, unsigned long long* h, uint32_t x,
                                  uint32_t y) {
@@ -375,23 +386,24 @@ __device__ void j2_walk_t(const View& v, const PairLinks& pl, const J2Ctx& c, ui
           const uint32_t z = v.g2_adj[pos];
           if (dt <= c.dO ? has2(v.hs2, c.o, z) : has2(v.hs2, t, z)) atomicAdd(&L.cnt[slot][2], 1u);
         } else {
-          uint32_t y;
+          uint32_t y, cy;
           if (dt <= n_t) {
             y = v.g2_adj[pos];
             if (y == c.s || y == c.o || !j2_in_t(v, c, y)) return;
+            cy = j2_cls(v, c, y);
           } else {
             y = j2_t_node(v, pl, c, pos);
             if (y == t || !has2(v.hs2, t, y)) return;
+            cy = j2_t_cls(pl, c, pos);
           }
-          const uint32_t cy = j2_cls(v, c, y);
           atomicAdd(&L.cnt[slot][3 + cy], 1u);
           if (y > t) atomicAdd(&L.cnt[slot][7 + cy], 1u);
         }
       },
       [&](uint32_t slot, uint32_t j) {
         const uint32_t t = j2_t_node(v, pl, c, c.tlo + j);
-        const uint32_t ts = has2(v.hs2, c.s, t), to = has2(v.hs2, c.o, t);
-        const uint32_t ct = ts | (to << 1);
+        const uint32_t ct = j2_t_cls(pl, c, c.tlo + j);
+        const uint32_t ts = ct & 1u, to = ct >> 1;
         const uint32_t dt = deg2_of(v, t);
         const uint32_t a_s = L.cnt[slot][0], a_so = L.cnt[slot][1], a_o = L.cnt[slot][2];
         const uint32_t c3 = a_so, c1 = a_s - to - a_so, c2 = a_o - ts - a_so;
@@ -535,7 +547,7 @@ __device__ void sample_j2_k4_sparse(const View& v, const PairLinks& pl, const No
     if (tid < 4) L.tcls[tid] = 0;
     __syncthreads();
     // class sizes of T
-    for (uint64_t p = c.tlo + tid; p < c.thi; p += kThreads) atomicAdd(&L.tcls[j2_cls(v, c, j2_t_node(v, pl, c, p))], 1u);
+    for (uint64_t p = c.tlo + tid; p < c.thi; p += kThreads) atomicAdd(&L.tcls[j2_t_cls(pl, c, p)], 1u);
     __syncthreads();
     const uint32_t tc1 = L.tcls[1], tc2 = L.tcls[2], tc3 = L.tcls[3];
     // ---- first term (all of A), less every pair inside T as if not joined
@@ -575,7 +587,8 @@ __device__ void sample_j2_k4_sparse(const View& v, const PairLinks& pl, const No
       hsub(lut, h, 1u | ((bb & 1u) << 2) | (((bb >> 1) & 1u) << 5) | ((bb >> 2) << 7), ns.h3[8ull * o + bb]);
     }
     // corrections: the hyperedges {s, o, t}
-    for (uint64_t p = c.tlo + tid; p < c.thi; p += kThreads) hadd(lut, h, j2_agg_pat(v, c, s, j2_t_node(v, pl, c, p)), 1);
+    for (uint64_t p = c.tlo + tid; p < c.thi; p += kThreads)
+      hadd(lut, h, j2_agg_pat_t(c, j2_t_node(v, pl, c, p), j2_t_cls(pl, c, p)), 1);
     // ---- the walks over T and over the corrections, and the hyperedges at s
     // and holding e: here when short, else queued
     const uint32_t n_r = ds + n_t;
