@@ -455,7 +455,9 @@ __device__ void j2_walk_r(const View& v, const PairLinks& pl, const J2Ctx& c, ui
       first, last, L,
       [&](uint32_t j, uint32_t* base, uint32_t* len) {
         const uint32_t y = y_of(j);
-        if (y == c.o || (j >= c.ds && has2(v.hs2, c.s, y))) return;
+        // a node of T: its pairs with s and o from the index entry
+        const uint32_t ycls = j < c.ds ? 0u : j2_t_cls(pl, c, c.tlo + (j - c.ds));
+        if (y == c.o || (ycls & 1u)) return;
         const unsigned long long ky =
             y < c.o ? (((unsigned long long)y << 32) | c.o) : (((unsigned long long)c.o << 32) | y);
         uint64_t lo;
@@ -465,7 +467,7 @@ __device__ void j2_walk_r(const View& v, const PairLinks& pl, const J2Ctx& c, ui
         // y ~ s holds exactly for the first part of the list (a node of T
         // adjacent to s was taken there); y is in T in the second part
         const uint32_t sy = j < c.ds, ty = j < c.ds ? uint32_t(j2_in_t(v, c, y)) : 1u;
-        const uint32_t oy = has2(v.hs2, c.o, y);
+        const uint32_t oy = j < c.ds ? uint32_t(has2(v.hs2, c.o, y)) : (ycls >> 1);
         L.cnt[threadIdx.x][0] = y;
         L.cnt[threadIdx.x][1] = sy | (oy << 1) | (ty << 2);
       },

@@ -276,3 +276,45 @@ def test_bit_row_option_bounds(hm):
         hm.hm_set_option(hm.HM_OPT_BITSET_MAX_NODES, 8193)
     with pytest.raises(hm.HMError):
         hm.hm_set_option(99, 0)
+
+
+def _hub_hypergraph(seed=11, n=150):
+    """Hubs 0 and 1 with more than 64 pairwise neighbours each, the pair {0, 1}
+    in 99 3-node hyperedges and {0, 2} in 38, and the 3-node hyperedge
+    {0, 1, 2} inside 88 4-node hyperedges, over random background hyperedges:
+    the exact step without bit rows meets lists both short enough to hold in
+    LDS and too long to."""
+    rng = np.random.default_rng(seed)
+    E = set()
+
+    def add(t):
+        E.add(tuple(sorted(int(x) for x in t)))
+
+    def count(k):
+        return sum(1 for e in E if len(e) == k)
+
+    for y in range(2, 91):
+        add((0, y))
+        add((1, y))
+    while count(2) < 700:
+        add(rng.choice(n, 2, replace=False))
+    for y in range(2, 101):
+        add((0, 1, y))
+    for y in range(3, 41):
+        add((0, 2, y))
+    target = count(3) + 300
+    while count(3) < target:
+        add(rng.choice(n, 3, replace=False))
+    for y in range(3, 91):
+        add((0, 1, 2, y))
+    target = count(4) + 200
+    while count(4) < target:
+        add(rng.choice(n, 4, replace=False))
+    return W.from_lists([list(e) for e in sorted(E)], n)
+
+
+@pytest.mark.parametrize("bit_rows", [True, False], ids=["bits", "hash"])
+def test_hub_lists_match_oracle(hm, bit_rows):
+    h = _hub_hypergraph()
+    for k in (3, 4):
+        assert np.array_equal(_gpu_counts(hm, h, k, bit_rows), core.count_exact(h, k)), k
