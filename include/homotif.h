@@ -308,10 +308,19 @@ int count_sampled_weighted_indices(const hm_graph* H, int k, const uint32_t* idx
  *                            graphs wait once the sizes are known and are
  *                            sized exactly.  0 builds every graph the second
  *                            way.  The graph does not depend on it.
+ *   HM_OPT_HUB_MIN_DEGREE     graphs without bit rows keep, from their first
+ *                            counting call on, a dense adjacency bit row for
+ *                            each node with at least this many pairwise
+ *                            neighbours (default 256), highest degrees first,
+ *                            within 32 MiB; pair tests against such a node
+ *                            read a bit instead of probing the hash set.  0
+ *                            keeps none.  Taken when a graph's rows are
+ *                            built; results do not depend on it.
  * HM_EINVAL for an unknown option or a value out of range. */
 #define HM_OPT_BITSET_MAX_NODES 1
 #define HM_OPT_SAMPLE_CHUNK_SCALE 2
 #define HM_OPT_ONE_PASS_MAX_EDGES 3
+#define HM_OPT_HUB_MIN_DEGREE 4
 int hm_set_option(int option, int64_t value);
 int hm_get_option(int option, int64_t* value);
 

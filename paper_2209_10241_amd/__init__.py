@@ -1,7 +1,7 @@
 """homotif: exact and hyperedge-sampled counting of higher-order motifs of
 order 3 and 4 on AMD MI355X, behind the C ABI of include/homotif.h."""
 from .binding import (  # noqa: F401
-    HM_ALLOC_PAPER, HM_ALLOC_PROPORTIONAL, HM_OPT_BITSET_MAX_NODES, HM_OPT_ONE_PASS_MAX_EDGES,
+    HM_ALLOC_PAPER, HM_ALLOC_PROPORTIONAL, HM_OPT_BITSET_MAX_NODES, HM_OPT_HUB_MIN_DEGREE, HM_OPT_ONE_PASS_MAX_EDGES,
     HM_OPT_SAMPLE_CHUNK_SCALE, count_nulls, count_sampled, count_sampled_indices,
     hm_null_export, hm_null_tile_sizes,
     Model, count_sampled_learned, count_sampled_weighted_indices, hm_contrib, hm_features, hm_mlp_forward,

@@ -141,6 +141,8 @@ std::atomic<uint32_t> g_sample_chunk_scale{1};
 uint32_t sample_chunk_scale() { return g_sample_chunk_scale.load(); }
 std::atomic<uint64_t> g_one_pass_max_edges{kOnePassMaxEdges};
 uint64_t one_pass_max_edges() { return g_one_pass_max_edges.load(); }
+std::atomic<uint32_t> g_hub_min_degree{kHubMinDegree};
+uint32_t hub_min_degree() { return g_hub_min_degree.load(); }
 
 const ClassTables& class_tables() {
   static const ClassTables t = build();
@@ -342,6 +344,14 @@ int hm_set_option(int option, int64_t value) {
     hm::g_one_pass_max_edges.store(uint64_t(value));
     return HM_OK;
   }
+  if (option == HM_OPT_HUB_MIN_DEGREE) {
+    if (value < 0 || value > int64_t(0xFFFFFFFFu)) {
+      hm::set_error("HM_OPT_HUB_MIN_DEGREE must be in [0, 2^32 - 1]");
+      return HM_EINVAL;
+    }
+    hm::g_hub_min_degree.store(uint32_t(value));
+    return HM_OK;
+  }
   hm::set_error("unknown option %d", option);
   return HM_EINVAL;
 }
@@ -361,6 +371,10 @@ int hm_get_option(int option, int64_t* value) {
   }
   if (option == HM_OPT_ONE_PASS_MAX_EDGES) {
     *value = int64_t(hm::g_one_pass_max_edges.load());
+    return HM_OK;
+  }
+  if (option == HM_OPT_HUB_MIN_DEGREE) {
+    *value = int64_t(hm::g_hub_min_degree.load());
     return HM_OK;
   }
   hm::set_error("unknown option %d", option);

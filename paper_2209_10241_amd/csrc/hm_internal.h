@@ -36,6 +36,12 @@ uint32_t sample_chunk_scale();
 // HM_OPT_ONE_PASS_MAX_EDGES)
 constexpr uint64_t kOnePassMaxEdges = 1ull << 20;
 uint64_t one_pass_max_edges();
+// graphs without bit rows keep a dense adjacency bit row for each node with
+// at least hub_min_degree() pairwise neighbours (HM_OPT_HUB_MIN_DEGREE; 0:
+// none), the highest degrees first, in at most kHubRowBytes
+constexpr uint32_t kHubMinDegree = 256;
+constexpr uint64_t kHubRowBytes = 32ull << 20;
+uint32_t hub_min_degree();
 
 // ----------------------------------------------------------------- errors
 void set_error(const char* fmt, ...);
@@ -200,6 +206,7 @@ void dfree_on(void* const* ps, size_t n, hipStream_t st);
 // into H->hist (case (a) is counted by the caller).
 int count_sparse(const hm_graph* H, int k, hipStream_t st);
 int ensure_pair_links(hm_graph* H, hipStream_t st);
+int ensure_hub_rows(hm_graph* H, hipStream_t st);
 int ensure_node_stats(hm_graph* H, hipStream_t st);
 int ensure_edge_stats(hm_graph* H, hipStream_t st);
 
@@ -272,6 +279,12 @@ struct hm_graph {
   // the 3-node hyperedges by decreasing estimated cost of their exact
   // neighbourhood count (built on first use without bit rows)
   uint32_t* b4_order = nullptr;
+  // dense adjacency bit rows of the highest-degree nodes (built on first use
+  // without bit rows): hub_rank[v] is v's row or -1; rows of hub_words words
+  int32_t* hub_rank = nullptr;
+  uint32_t* hub_bits = nullptr;
+  uint32_t hub_words = 0;
+  bool hub_built = false;
   // per node, built on first use without bit rows: triangles at the node, sum
   // of its neighbours' degrees, its 3-node hyperedges by pairwise pattern (8)
   unsigned long long* ns_tri = nullptr;

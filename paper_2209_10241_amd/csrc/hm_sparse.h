@@ -40,7 +40,19 @@ struct PairLinks {
   // adjacency to the key's nodes (bit 0: x ~ t, bit 1: y ~ t)
   const uint32_t* third;
   const uint8_t* adj;
+  // dense adjacency rows of the highest-degree nodes: hub_rank[v] is v's row
+  // (hub_w words at hub_bits + row * hub_w) or -1; hub_rank null: none
+  const int32_t* hub_rank;
+  const uint32_t* hub_bits;
+  uint32_t hub_w;
 };
+
+// The dense adjacency row of x, or -1.
+__device__ inline int hub_of(const PairLinks& pl, uint32_t x) { return pl.hub_rank ? pl.hub_rank[x] : -1; }
+// Whether z is a pairwise neighbour of the node with dense row r.
+__device__ inline uint32_t hub_adj(const PairLinks& pl, int r, uint32_t z) {
+  return (pl.hub_bits[uint64_t(r) * pl.hub_w + (z >> 5)] >> (z & 31)) & 1u;
+}
 
 // Run [*lo, *lo + *len) of pl.keys holding `key` (empty when absent).
 __device__ inline void pl_find(const PairLinks& pl, unsigned long long key, uint64_t* lo, uint32_t* len) {
@@ -100,6 +112,7 @@ __device__ inline uint32_t row_count(const View& v, uint32_t s, uint32_t x) {
 // {b,c}; slot 3 the 4-node hyperedges of the member with the fewest of them.
 struct B4Ctx {
   uint32_t a, b, c, base_p;
+  int ra, rb, rc;   // dense adjacency rows of a, b, c, or -1
   // named scalars, not arrays: a dynamically indexed array would live in scratch
   uint64_t lo0, lo1, lo2, lo3, len0, len1, len2, len3, total;
 };
@@ -124,6 +137,9 @@ __device__ __forceinline__ B4Ctx b4_ctx(const View& v, const PairLinks& pl, uint
   const uint32_t m4 = (fa <= fb && fa <= fc) ? a : (fb <= fc ? b : c);
   x.lo3 = v.i4_off[m4];
   x.len3 = v.i4_off[m4 + 1] - x.lo3;
+  x.ra = int(uniform_u32(uint32_t(hub_of(pl, a))));
+  x.rb = int(uniform_u32(uint32_t(hub_of(pl, b))));
+  x.rc = int(uniform_u32(uint32_t(hub_of(pl, c))));
   // the same in every lane: kept in scalar registers
   x.base_p = uniform_u32(x.base_p);
   x.lo0 = uniform_u64(x.lo0);
@@ -160,10 +176,14 @@ __device__ __forceinline__ void b4_combo_counts(const View& v, const PairLinks& 
   }
   uint32_t n1x = 0, n1y = 0, n1xy = 0;
   const uint32_t b1 = v.g2_off[r1], l1 = v.g2_off[r1 + 1] - b1;
+  const int hx1 = x1 == a ? x.ra : (x1 == b ? x.rb : x.rc), hy1 = y1 == a ? x.ra : (y1 == b ? x.rb : x.rc);
   for (uint32_t t = lane; t < l1; t += kWave) {
     const uint32_t z = v.g2_adj[b1 + t];
-    const Probe64 px = probe2_start(v.hs2, x1, z), py = probe2_start(v.hs2, y1, z);
-    const uint32_t hx = probe64_end(v.hs2, px), hy = probe64_end(v.hs2, py);
+    Probe64 px, py;
+    if (hx1 < 0) px = probe2_start(v.hs2, x1, z);
+    if (hy1 < 0) py = probe2_start(v.hs2, y1, z);
+    const uint32_t hx = hx1 >= 0 ? hub_adj(pl, hx1, z) : uint32_t(probe64_end(v.hs2, px));
+    const uint32_t hy = hy1 >= 0 ? hub_adj(pl, hy1, z) : uint32_t(probe64_end(v.hs2, py));
     n1x += hx;
     n1y += hy;
     n1xy += hx & hy;
@@ -315,14 +335,15 @@ __device__ __forceinline__ uint32_t b4_exception(const View& v, const PairLinks&
       if (slot == 2 && !hac) qac = probe3_start(v.hs3, a, c, y);
       // m's neighbours, when held: c's for slot 0, b's for slot 1, a's for slot 2
       const bool hm = slot == 0 ? hc : (slot == 1 ? hb : ha);
+      const int rm = slot == 0 ? x.rc : (slot == 1 ? x.rb : x.ra);
       Probe64 pm;
-      if (!hm) pm = probe2_start(v.hs2, m, y);
+      if (!hm && rm < 0) pm = probe2_start(v.hs2, m, y);
       if (slot >= 1 && (hab ? in_short(sh->mem, sh->n_ab, y) : probe128_end(v.hs3, qab))) return 0;
       if (slot == 2 && (hac ? in_short(sh->mem + kB4ShortRun, sh->n_ac, y) : probe128_end(v.hs3, qac))) return 0;
       const uint32_t mv =
           hm ? uint32_t(in_short(sh->mem + kB4AdjAt + (2 - uint32_t(slot)) * kB4ShortAdj,
                                  slot == 0 ? sh->n_c : (slot == 1 ? sh->n_b : sh->n_a), y))
-             : uint32_t(probe64_end(v.hs2, pm));
+             : (rm >= 0 ? hub_adj(pl, rm, y) : uint32_t(probe64_end(v.hs2, pm)));
       const uint32_t lo = pair_adj & 1u, hi = pair_adj >> 1;
       const uint32_t av = slot == 2 ? mv : lo;
       const uint32_t bv = slot == 0 ? hi : (slot == 1 ? mv : lo);
@@ -354,9 +375,9 @@ __device__ __forceinline__ uint32_t b4_exception(const View& v, const PairLinks&
   }
   // y's pairs with the two members of the slot's pair come with the entry
   Probe64 pa, pb, pc;
-  if ((slot == 2 || slot == 3) && !ha) pa = probe2_start(v.hs2, a, y);
-  if ((slot == 1 || slot == 3) && !hb) pb = probe2_start(v.hs2, b, y);
-  if ((slot == 0 || slot == 3) && !hc) pc = probe2_start(v.hs2, c, y);
+  if ((slot == 2 || slot == 3) && !ha && x.ra < 0) pa = probe2_start(v.hs2, a, y);
+  if ((slot == 1 || slot == 3) && !hb && x.rb < 0) pb = probe2_start(v.hs2, b, y);
+  if ((slot == 0 || slot == 3) && !hc && x.rc < 0) pc = probe2_start(v.hs2, c, y);
   const uint32_t abv =
       slot == 0 ? 1u : uint32_t(hab ? in_short(sh->mem, sh->n_ab, y) : probe128_end(v.hs3, pab));
   const uint32_t acv =
@@ -369,18 +390,21 @@ __device__ __forceinline__ uint32_t b4_exception(const View& v, const PairLinks&
   if (slot == 3 && (abv || acv || bcv)) return 0;
   const uint32_t quad =
       slot == 3 ? 1u : uint32_t(hq ? in_short(sh->mem + kB4QAt, sh->n_q, y) : probe128_end(v.hs4, pq));
-  const uint32_t av = slot == 0 || slot == 1
-                          ? (pair_adj & 1u)
-                          : uint32_t(ha ? in_short(sh->mem + kB4AdjAt, sh->n_a, y) : probe64_end(v.hs2, pa));
+  const uint32_t av =
+      slot == 0 || slot == 1
+          ? (pair_adj & 1u)
+          : (ha ? uint32_t(in_short(sh->mem + kB4AdjAt, sh->n_a, y))
+                : (x.ra >= 0 ? hub_adj(pl, x.ra, y) : uint32_t(probe64_end(v.hs2, pa))));
   const uint32_t bv =
       slot == 0 ? (pair_adj >> 1)
                 : (slot == 2 ? (pair_adj & 1u)
-                             : uint32_t(hb ? in_short(sh->mem + kB4AdjAt + kB4ShortAdj, sh->n_b, y)
-                                           : probe64_end(v.hs2, pb)));
-  const uint32_t cv = slot == 1 || slot == 2
-                          ? (pair_adj >> 1)
-                          : uint32_t(hc ? in_short(sh->mem + kB4AdjAt + 2 * kB4ShortAdj, sh->n_c, y)
-                                        : probe64_end(v.hs2, pc));
+                             : (hb ? uint32_t(in_short(sh->mem + kB4AdjAt + kB4ShortAdj, sh->n_b, y))
+                                   : (x.rb >= 0 ? hub_adj(pl, x.rb, y) : uint32_t(probe64_end(v.hs2, pb)))));
+  const uint32_t cv =
+      slot == 1 || slot == 2
+          ? (pair_adj >> 1)
+          : (hc ? uint32_t(in_short(sh->mem + kB4AdjAt + 2 * kB4ShortAdj, sh->n_c, y))
+                : (x.rc >= 0 ? hub_adj(pl, x.rc, y) : uint32_t(probe64_end(v.hs2, pc))));
   const uint32_t combo = av | (bv << 1) | (cv << 2);
   bool counted = !quad;   // a 4-node hyperedge: counted on its own, or larger than a sampled 3-node one
   if (OWN && counted) {

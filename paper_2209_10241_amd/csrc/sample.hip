@@ -271,6 +271,7 @@ __device__ void block_flat(uint32_t first, uint32_t last, J2SparseLds& L, Seg se
 
 struct J2Ctx {
   uint32_t e0, s, o, ds, dO;
+  int rs, ro;   // dense adjacency rows of s and o, or -1
   uint64_t tlo, thi;
   bool any_t;
   unsigned long long na[4];
@@ -286,6 +287,8 @@ __device__ inline J2Ctx j2_ctx(const View& v, const PairLinks& pl, const unsigne
   c.o = d0 <= d1 ? e1 : e0;
   c.ds = d0 <= d1 ? d0 : d1;
   c.dO = d0 <= d1 ? d1 : d0;
+  c.rs = hub_of(pl, c.s);
+  c.ro = hub_of(pl, c.o);
   const unsigned long long key = ((unsigned long long)e0 << 32) | e1;
   uint32_t nt;
   pl_find(pl, key, &c.tlo, &nt);
@@ -313,8 +316,15 @@ __device__ inline void hadd(const uint8_t* lut, unsigned long long* h, uint32_t 
 __device__ inline bool j2_in_t(const View& v, const J2Ctx& c, uint32_t y) {
   return c.any_t && has3(v.hs3, c.s, c.o, y);
 }
-__device__ inline uint32_t j2_cls(const View& v, const J2Ctx& c, uint32_t y) {
-  return has2(v.hs2, c.s, y) | (has2(v.hs2, c.o, y) << 1);
+// s ~ z and o ~ z, from the dense rows of s and o when they have them
+__device__ inline uint32_t j2_s_adj(const View& v, const PairLinks& pl, const J2Ctx& c, uint32_t z) {
+  return c.rs >= 0 ? hub_adj(pl, c.rs, z) : uint32_t(has2(v.hs2, c.s, z));
+}
+__device__ inline uint32_t j2_o_adj(const View& v, const PairLinks& pl, const J2Ctx& c, uint32_t z) {
+  return c.ro >= 0 ? hub_adj(pl, c.ro, z) : uint32_t(has2(v.hs2, c.o, z));
+}
+__device__ inline uint32_t j2_cls(const View& v, const PairLinks& pl, const J2Ctx& c, uint32_t y) {
+  return j2_s_adj(v, pl, c, y) | (j2_o_adj(v, pl, c, y) << 1);
 }
 __device__ inline uint32_t j2_t_node(const View& v, const PairLinks& pl, const J2Ctx& c, uint64_t p) {
   return pl.third[p];
@@ -377,20 +387,20 @@ __device__ void j2_walk_t(const View& v, const PairLinks& pl, const J2Ctx& c, ui
         const uint32_t dt = deg2_of(v, t);
         if (sg == 0) {
           const uint32_t z = v.g2_adj[pos];
-          const uint32_t hit = dt <= c.ds ? has2(v.hs2, c.s, z) : has2(v.hs2, t, z);
+          const uint32_t hit = dt <= c.ds ? j2_s_adj(v, pl, c, z) : uint32_t(has2(v.hs2, t, z));
           if (hit) {
             atomicAdd(&L.cnt[slot][0], 1u);
-            if (has2(v.hs2, c.o, z)) atomicAdd(&L.cnt[slot][1], 1u);
+            if (j2_o_adj(v, pl, c, z)) atomicAdd(&L.cnt[slot][1], 1u);
           }
         } else if (sg == 1) {
           const uint32_t z = v.g2_adj[pos];
-          if (dt <= c.dO ? has2(v.hs2, c.o, z) : has2(v.hs2, t, z)) atomicAdd(&L.cnt[slot][2], 1u);
+          if (dt <= c.dO ? j2_o_adj(v, pl, c, z) : uint32_t(has2(v.hs2, t, z))) atomicAdd(&L.cnt[slot][2], 1u);
         } else {
           uint32_t y, cy;
           if (dt <= n_t) {
             y = v.g2_adj[pos];
             if (y == c.s || y == c.o || !j2_in_t(v, c, y)) return;
-            cy = j2_cls(v, c, y);
+            cy = j2_cls(v, pl, c, y);
           } else {
             y = j2_t_node(v, pl, c, pos);
             if (y == t || !has2(v.hs2, t, y)) return;
@@ -467,7 +477,7 @@ __device__ void j2_walk_r(const View& v, const PairLinks& pl, const J2Ctx& c, ui
         // y ~ s holds exactly for the first part of the list (a node of T
         // adjacent to s was taken there); y is in T in the second part
         const uint32_t sy = j < c.ds, ty = j < c.ds ? uint32_t(j2_in_t(v, c, y)) : 1u;
-        const uint32_t oy = j < c.ds ? uint32_t(has2(v.hs2, c.o, y)) : (ycls >> 1);
+        const uint32_t oy = j < c.ds ? j2_o_adj(v, pl, c, y) : (ycls >> 1);
         L.cnt[threadIdx.x][0] = y;
         L.cnt[threadIdx.x][1] = sy | (oy << 1) | (ty << 2);
       },
@@ -479,11 +489,12 @@ __device__ void j2_walk_r(const View& v, const PairLinks& pl, const J2Ctx& c, ui
         // o ~ z and y ~ z come with the entry (its key is the pair {o, y})
         const uint32_t za = pl.adj[r];
         const uint32_t oz = c.o < y ? (za & 1u) : (za >> 1), yz = c.o < y ? (za >> 1) : (za & 1u);
-        const Probe64 psz = probe2_start(v.hs2, c.s, z);
+        Probe64 psz;
+        if (c.rs < 0) psz = probe2_start(v.hs2, c.s, z);
         const Probe128 psyz = probe3_start(v.hs3, c.s, y, z);
         Probe128 ptz;
         if (c.any_t) ptz = probe3_start(v.hs3, c.s, c.o, z);
-        const uint32_t sz = probe64_end(v.hs2, psz);
+        const uint32_t sz = c.rs >= 0 ? hub_adj(pl, c.rs, z) : uint32_t(probe64_end(v.hs2, psz));
         const uint32_t tz = c.any_t && probe128_end(v.hs3, ptz);
         if (z < y && (sz | tz)) return;   // taken from z
         // as the histogram at o counts it (the smaller node first)
@@ -1067,6 +1078,7 @@ int launch_sampled(const hm_graph* H, int k, const uint32_t* const idx[5], const
     HM_TRY(ensure_pair_links(const_cast<hm_graph*>(H), st));
     HM_TRY(ensure_node_stats(const_cast<hm_graph*>(H), st));
     HM_TRY(ensure_edge_stats(const_cast<hm_graph*>(H), st));
+    HM_TRY(ensure_hub_rows(const_cast<hm_graph*>(H), st));
   }
   SampledArgs a;
   a.v = view_of(H);
@@ -1078,6 +1090,9 @@ int launch_sampled(const hm_graph* H, int k, const uint32_t* const idx[5], const
   a.pl.codeg = H->pl_codeg;
   a.pl.third = H->pl_third;
   a.pl.adj = H->pl_adj;
+  a.pl.hub_rank = H->hub_rank;
+  a.pl.hub_bits = H->hub_bits;
+  a.pl.hub_w = H->hub_words;
   a.ns.tri = H->ns_tri;
   a.ns.nbr = H->ns_nbr;
   a.ns.h3 = H->ns_h3;

@@ -701,7 +701,85 @@ PairLinks pair_links_of(const hm_graph* H) {
   pl.codeg = H->pl_codeg;
   pl.third = H->pl_third;
   pl.adj = H->pl_adj;
+  pl.hub_rank = H->hub_rank;
+  pl.hub_bits = H->hub_bits;
+  pl.hub_w = H->hub_words;
   return pl;
+}
+
+// One workgroup per dense row: the bits of the node's pairwise neighbours.
+__global__ void k_hub_rows(const uint32_t* __restrict__ g2_off, const uint32_t* __restrict__ g2_adj,
+                           const uint32_t* __restrict__ hubs, uint32_t n_hub, uint32_t words,
+                           uint32_t* __restrict__ bits) {
+  for (uint32_t r = blockIdx.x; r < n_hub; r += gridDim.x) {
+    const uint32_t x = hubs[r];
+    uint32_t* row = bits + uint64_t(r) * words;
+    for (uint32_t p = g2_off[x] + threadIdx.x; p < g2_off[x + 1]; p += blockDim.x) {
+      const uint32_t z = g2_adj[p];
+      atomicOr(&row[z >> 5], 1u << (z & 31));
+    }
+  }
+}
+
+// H->hub_rank and H->hub_bits: the nodes with at least hub_min_degree()
+// pairwise neighbours, highest degree first (ties by id), as many as fit in
+// kHubRowBytes.  Built once per graph.
+int ensure_hub_rows(hm_graph* H, hipStream_t st) {
+  note_use(H, st);
+  if (H->hub_built) return HM_OK;
+  const uint32_t n = H->n_nodes, min_deg = hub_min_degree();
+  const uint32_t words = (n + 31) / 32;
+  if (n == 0 || min_deg == 0 || !H->g2_off) {
+    H->hub_built = true;
+    return HM_OK;
+  }
+  std::vector<uint32_t> off(size_t(n) + 1);
+  HM_HIP(hipMemcpyAsync(off.data(), H->g2_off, off.size() * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+  HM_HIP(hipStreamSynchronize(st));
+  std::vector<uint32_t> hubs;
+  for (uint32_t x = 0; x < n; ++x)
+    if (off[x + 1] - off[x] >= min_deg) hubs.push_back(x);
+  std::sort(hubs.begin(), hubs.end(), [&](uint32_t p, uint32_t q) {
+    const uint32_t dp = off[p + 1] - off[p], dq = off[q + 1] - off[q];
+    return dp != dq ? dp > dq : p < q;
+  });
+  const uint64_t max_rows = kHubRowBytes / (uint64_t(words) * sizeof(uint32_t));
+  if (hubs.size() > max_rows) hubs.resize(size_t(max_rows));
+  if (hubs.empty()) {
+    H->hub_built = true;
+    return HM_OK;
+  }
+  std::vector<int32_t> rank(n, -1);
+  for (size_t r = 0; r < hubs.size(); ++r) rank[hubs[r]] = int32_t(r);
+  const uint32_t n_hub = uint32_t(hubs.size());
+  void *rank_d = nullptr, *hubs_d = nullptr, *bits_d = nullptr;
+  int rc = dalloc(&rank_d, size_t(n) * sizeof(int32_t));
+  if (rc == HM_OK) rc = dalloc(&hubs_d, size_t(n_hub) * sizeof(uint32_t));
+  if (rc == HM_OK) rc = dalloc(&bits_d, size_t(n_hub) * words * sizeof(uint32_t));
+  if (rc == HM_OK && (hipMemcpyAsync(rank_d, rank.data(), rank.size() * sizeof(int32_t), hipMemcpyHostToDevice, st) !=
+                          hipSuccess ||
+                      hipMemcpyAsync(hubs_d, hubs.data(), hubs.size() * sizeof(uint32_t), hipMemcpyHostToDevice, st) !=
+                          hipSuccess))
+    rc = HM_EDEVICE;
+  if (rc == HM_OK) rc = fill_u32(static_cast<uint32_t*>(bits_d), 0, uint64_t(n_hub) * words, st);
+  if (rc == HM_OK) {
+    k_hub_rows<<<std::min<uint32_t>(n_hub, 4096), 256, 0, st>>>(H->g2_off, H->g2_adj, static_cast<const uint32_t*>(hubs_d),
+                                                               n_hub, words, static_cast<uint32_t*>(bits_d));
+    if (hipGetLastError() != hipSuccess) rc = HM_EDEVICE;
+  }
+  // the host vectors stay alive until the copies have run
+  if (hipStreamSynchronize(st) != hipSuccess && rc == HM_OK) rc = HM_EDEVICE;
+  dfree(hubs_d);
+  if (rc != HM_OK) {
+    dfree(rank_d);
+    dfree(bits_d);
+    return rc;
+  }
+  H->hub_rank = static_cast<int32_t*>(rank_d);
+  H->hub_bits = static_cast<uint32_t*>(bits_d);
+  H->hub_words = words;
+  H->hub_built = true;
+  return HM_OK;
 }
 
 // H->b4_order, after the pair index: the 3-node hyperedges sorted by
@@ -806,6 +884,7 @@ int count_sparse(const hm_graph* H, int k, hipStream_t st) {
   if (k == 4 && n3) {
     HM_TRY(ensure_pair_links(const_cast<hm_graph*>(H), st));
     HM_TRY(ensure_b4_order(const_cast<hm_graph*>(H), st));
+    HM_TRY(ensure_hub_rows(const_cast<hm_graph*>(H), st));
     // no more workgroups than are resident at once: each wavefront's share is
     // fixed, and a workgroup that starts late would finish late
     const unsigned grid = grid_cap(n3, kWavesPerBlock, resident_blocks(reinterpret_cast<const void*>(k_sp_b4)));

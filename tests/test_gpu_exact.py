@@ -318,3 +318,32 @@ def test_hub_lists_match_oracle(hm, bit_rows):
     h = _hub_hypergraph()
     for k in (3, 4):
         assert np.array_equal(_gpu_counts(hm, h, k, bit_rows), core.count_exact(h, k)), k
+
+
+@pytest.fixture
+def hub_rows(hm):
+    """Dense adjacency rows for every node with at least 2 pairwise
+    neighbours, so that the bit-free kernels read rows instead of probing."""
+    hm.hm_set_option(hm.HM_OPT_HUB_MIN_DEGREE, 2)
+    try:
+        yield
+    finally:
+        hm.hm_set_option(hm.HM_OPT_HUB_MIN_DEGREE, 256)
+
+
+def test_hub_rows_match_oracle(hm, hub_rows):
+    h = _hub_hypergraph()
+    assert np.array_equal(_gpu_counts(hm, h, 4, bit_rows=False), core.count_exact(h, 4))
+    h = W.scaled_communication(0.004, 0)
+    assert np.array_equal(_gpu_counts(hm, h, 4, bit_rows=False), _golden("communication_scaled_0.004", 4))
+    for seed in range(6):
+        h = W.random_small(7100 + seed, 30 + 9 * seed, 200 + 60 * seed, {2: 0.5, 3: 0.35, 4: 0.15})
+        assert np.array_equal(_gpu_counts(hm, h, 4, bit_rows=False), core.count_exact(h, 4)), seed
+
+
+def test_hub_option_bounds(hm):
+    with pytest.raises(hm.HMError):
+        hm.hm_set_option(hm.HM_OPT_HUB_MIN_DEGREE, -1)
+    with pytest.raises(hm.HMError):
+        hm.hm_set_option(hm.HM_OPT_HUB_MIN_DEGREE, 1 << 32)
+    assert hm.hm_get_option(hm.HM_OPT_HUB_MIN_DEGREE) == 256

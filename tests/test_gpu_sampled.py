@@ -228,3 +228,34 @@ def test_chunk_scale_option_bounds(hm):
         with pytest.raises(hm.HMError):
             hm.hm_set_option(hm.HM_OPT_SAMPLE_CHUNK_SCALE, bad)
     hm.hm_set_option(hm.HM_OPT_SAMPLE_CHUNK_SCALE, 1)
+
+
+@pytest.fixture
+def hub_rows(hm):
+    """Dense adjacency rows for every node with at least 2 pairwise neighbours."""
+    hm.hm_set_option(hm.HM_OPT_HUB_MIN_DEGREE, 2)
+    try:
+        yield
+    finally:
+        hm.hm_set_option(hm.HM_OPT_HUB_MIN_DEGREE, 256)
+
+
+def test_hub_rows_heavy_tailed(hm, hub_rows, queued):
+    h = W.scaled_communication(0.004, 0)
+    nh = core.normalise(h)
+    want_raw, want_est, _, _ = _oracle_sampled(nh, 4, 0.2, 31)
+    with _graph(hm, h, False) as g:
+        est, raw = hm.count_sampled(g, 4, 0.2, 31, 0)
+    assert np.array_equal(raw.cpu().numpy(), want_raw)
+    assert np.array_equal(est.cpu().numpy(), want_est)
+
+
+def test_hub_rows_census(hm, hub_rows):
+    h = W.scaled_communication(0.004, 0)
+    exact = _golden("communication_scaled_0.004", 4)
+    with _graph(hm, h, False) as g:
+        st = g.stats()
+        samples = {j: np.arange(st[f"n{j}"]) for j in range(2, 5)}
+        est, raw = hm.count_sampled_indices(g, 4, samples)
+        countmax = np.array([hm.hm_class_info(4, c)[2] for c in range(len(exact))])
+    assert np.array_equal(raw.cpu().numpy(), exact * countmax)
