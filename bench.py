@@ -36,6 +36,10 @@ SHORT_RUN = 64
 SHORT_Q = 16
 # longest pairwise row of a member of that hyperedge it holds in LDS
 SHORT_ADJ = 64
+# nodes with at least this many pairwise neighbours keep a dense adjacency
+# row, highest degrees first, within HUB_ROW_BYTES
+HUB_MIN_DEGREE = 256
+HUB_ROW_BYTES = 32 << 20
 # integer VALU issue rate: 256 CUs x 64 lanes per cycle x 2.4 GHz
 ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 
@@ -65,7 +69,8 @@ def _unit_counts(e2: np.ndarray, e3: np.ndarray, n_nodes: int, words: int) -> di
     return {"c4_word_tasks": int(ys) * words, "b4_word_tasks": int(len(e3)) * words, "b4_candidates": cand}
 
 
-def _b4_lookup_model(e2: np.ndarray, e3: np.ndarray, e4: np.ndarray, n_nodes: int) -> dict:
+def _b4_lookup_model(e2: np.ndarray, e3: np.ndarray, e4: np.ndarray, n_nodes: int,
+                     hub_min_degree: int = HUB_MIN_DEGREE) -> dict:
     """Memory transactions of the 3-node-hyperedge fill-in step without bit
     rows (one wavefront per 3-node hyperedge e = {a<b<c}), counted from the
     strata.  Per e: 3 pair probes for e's own pattern, 3 pair-index lookups
@@ -80,10 +85,13 @@ def _b4_lookup_model(e2: np.ndarray, e3: np.ndarray, e4: np.ndarray, n_nodes: in
     {m, y}; else the pair {m, y} and the 3-node memberships of the pairs
     before P.  Per 4-node hyperedge holding e: its three 3-node memberships
     and three pairs.  A pair with a member of e whose pairwise row has at
-    most SHORT_ADJ entries (held in LDS) is a comparison.  Streamed bytes: 4
-    per row entry, 5 per pair-index entry (third node and its adjacency), 20
-    per entry of the 4-node incidence list read, 60 for e and its row
-    bounds, and the short lists and rows read once more into LDS."""
+    most SHORT_ADJ entries (held in LDS) is a comparison; with a member that
+    has a dense adjacency row (at least hub_min_degree neighbours, highest
+    degrees first within HUB_ROW_BYTES) it is one streamed 4-byte word.
+    Streamed bytes: 4 per row entry, 5 per pair-index entry (third node and
+    its adjacency), 20 per entry of the 4-node incidence list read, 60 for e
+    and its row bounds, the short lists and rows read once more into LDS,
+    and the dense-row words."""
     n = np.int64(n_nodes)
     if len(e3) == 0:
         return {"probes": 0, "stream_bytes": 0, "hyperedges": 0, "entries": 0}
@@ -91,6 +99,12 @@ def _b4_lookup_model(e2: np.ndarray, e3: np.ndarray, e4: np.ndarray, n_nodes: in
     t = e3.astype(np.int64)
     a, b, c = t[:, 0], t[:, 1], t[:, 2]
     dmin = np.minimum(np.minimum(deg2[a], deg2[b]), deg2[c])
+    # nodes with a dense adjacency row
+    hub = np.zeros(n_nodes, dtype=bool)
+    if hub_min_degree > 0:
+        cand = np.nonzero(deg2 >= hub_min_degree)[0]
+        cand = cand[np.lexsort((cand, -deg2[cand]))]
+        hub[cand[: HUB_ROW_BYTES // (4 * ((n_nodes + 31) // 32))]] = True
     # 3-node hyperedges on each pair (ab, ac, bc), and how many of their
     # third nodes lie below the member of e outside the pair
     pk = np.concatenate([a * n + b, a * n + c, b * n + c])
@@ -119,16 +133,30 @@ def _b4_lookup_model(e2: np.ndarray, e3: np.ndarray, e4: np.ndarray, n_nodes: in
     q_held = (len3 <= 64) & (holding <= SHORT_Q)
     qp = (~q_held).astype(np.int64)
     ab, ac, bc = probed
-    # pairs with a member of e are comparisons when its pairwise row is held
+    # pairs with a member of e are comparisons when its pairwise row is held,
+    # dense-row words when it has one, probes otherwise
     da, db, dc = deg2[a], deg2[b], deg2[c]
-    pa, pb, pc = ((d > SHORT_ADJ).astype(np.int64) for d in (da, db, dc))
-    probes = (7 + 2 * dmin
+    ha, hb, hc = hub[a].astype(np.int64), hub[b].astype(np.int64), hub[c].astype(np.int64)
+    pa, pb, pc = ((d > SHORT_ADJ).astype(np.int64) * (1 - h) for d, h in ((da, ha), (db, hb), (dc, hc)))
+    # the shortest row is walked against the other two members
+    r_a = (da <= db) & (da <= dc)
+    r_b = ~r_a & (db <= dc)
+    x_hub = np.where(r_a, hb, ha)              # first other member: b when a is walked, else a
+    y_hub = np.where(r_a | r_b, hc, hb)        # second: c unless c is walked
+    walk_probes = dmin * ((1 - x_hub) + (1 - y_hub))
+    walk_words = dmin * (x_hub + y_hub)
+    # (a held row takes precedence over a dense one)
+    wa, wb, wc = (h * (d > SHORT_ADJ).astype(np.int64) for d, h in ((da, ha), (db, hb), (dc, hc)))
+    pair_words = (late[0] + below[0]) * wc + (late[1] + below[1]) * wb + (late[2] + below[2]) * wa \
+        + holding * (wa + wb + wc)
+    probes = (7 + walk_probes
               + late[0] * (ac + bc + qp + pc) + late[1] * (ab + bc + qp + pb) + late[2] * (ab + ac + qp + pa)
               + below[0] * pc + below[1] * (ab + pb) + below[2] * (ab + ac + pa)
               + holding * (ab + ac + bc + pa + pb + pc)).sum()
     held_rows = sum(np.where(d <= SHORT_ADJ, d, 0) for d in (da, db, dc))
     stream = (4 * dmin + 5 * L.sum(axis=0) + 20 * len3 + 60
-              + 4 * (L * (1 - probed)).sum(axis=0) + 20 * np.where(len3 <= 64, len3, 0) + 4 * held_rows).sum()
+              + 4 * (L * (1 - probed)).sum(axis=0) + 20 * np.where(len3 <= 64, len3, 0) + 4 * held_rows
+              + 4 * (walk_words + pair_words)).sum()
     # positions the exception loops walk: every entry of the three pair runs
     # and of the 4-node incidence list read
     entries = int(L.sum() + len3.sum())
