@@ -176,7 +176,8 @@ __device__ __forceinline__ void b4_combo_counts(const View& v, const PairLinks& 
   }
   uint32_t n1x = 0, n1y = 0, n1xy = 0;
   const uint32_t b1 = v.g2_off[r1], l1 = v.g2_off[r1 + 1] - b1;
-  const int hx1 = x1 == a ? x.ra : (x1 == b ? x.rb : x.rc), hy1 = y1 == a ? x.ra : (y1 == b ? x.rb : x.rc);
+  const int ra = x.ra, rb = x.rb, rc = x.rc;
+  const int hx1 = x1 == a ? ra : (x1 == b ? rb : rc), hy1 = y1 == a ? ra : (y1 == b ? rb : rc);
   for (uint32_t t = lane; t < l1; t += kWave) {
     const uint32_t z = v.g2_adj[b1 + t];
     Probe64 px, py;
@@ -231,6 +232,14 @@ struct B4Short {
   uint32_t n_ab, n_ac, n_bc, n_q;
   uint32_t n_a, n_b, n_c;   // pairwise neighbours of a, b, c
 };
+
+// No list held: every membership test probes.
+__device__ __forceinline__ B4Short b4_short_none() {
+  B4Short s;
+  s.mem = nullptr;
+  s.n_ab = s.n_ac = s.n_bc = s.n_q = s.n_a = s.n_b = s.n_c = kB4NotHeld;
+  return s;
+}
 
 __device__ __forceinline__ bool in_short(const uint32_t* l, uint32_t n, uint32_t y) {
   bool r = false;
@@ -297,11 +306,12 @@ __device__ __forceinline__ B4Short b4_short(const View& v, const PairLinks& pl, 
 // lists it holds replace the corresponding probes.
 template <bool OWN>
 __device__ __forceinline__ uint32_t b4_exception(const View& v, const PairLinks& pl, const B4Ctx& x, uint64_t t,
-                                        uint32_t* pat, const B4Short* sh = nullptr) {
+                                        uint32_t* pat, const B4Short& sh) {
   const uint32_t a = x.a, b = x.b, c = x.c;
-  const bool hab = sh && sh->n_ab != kB4NotHeld, hac = sh && sh->n_ac != kB4NotHeld,
-             hbc = sh && sh->n_bc != kB4NotHeld, hq = sh && sh->n_q != kB4NotHeld;
-  const bool ha = sh && sh->n_a != kB4NotHeld, hb = sh && sh->n_b != kB4NotHeld, hc = sh && sh->n_c != kB4NotHeld;
+  const bool hab = sh.n_ab != kB4NotHeld, hac = sh.n_ac != kB4NotHeld, hbc = sh.n_bc != kB4NotHeld,
+             hq = sh.n_q != kB4NotHeld;
+  const bool ha = sh.n_a != kB4NotHeld, hb = sh.n_b != kB4NotHeld, hc = sh.n_c != kB4NotHeld;
+  const int ra = x.ra, rb = x.rb, rc = x.rc;
   // slot and offset of t, with constant indices only (registers)
   int slot;
   uint64_t p;
@@ -335,14 +345,14 @@ __device__ __forceinline__ uint32_t b4_exception(const View& v, const PairLinks&
       if (slot == 2 && !hac) qac = probe3_start(v.hs3, a, c, y);
       // m's neighbours, when held: c's for slot 0, b's for slot 1, a's for slot 2
       const bool hm = slot == 0 ? hc : (slot == 1 ? hb : ha);
-      const int rm = slot == 0 ? x.rc : (slot == 1 ? x.rb : x.ra);
+      const int rm = slot == 0 ? rc : (slot == 1 ? rb : ra);
       Probe64 pm;
       if (!hm && rm < 0) pm = probe2_start(v.hs2, m, y);
-      if (slot >= 1 && (hab ? in_short(sh->mem, sh->n_ab, y) : probe128_end(v.hs3, qab))) return 0;
-      if (slot == 2 && (hac ? in_short(sh->mem + kB4ShortRun, sh->n_ac, y) : probe128_end(v.hs3, qac))) return 0;
+      if (slot >= 1 && (hab ? in_short(sh.mem, sh.n_ab, y) : probe128_end(v.hs3, qab))) return 0;
+      if (slot == 2 && (hac ? in_short(sh.mem + kB4ShortRun, sh.n_ac, y) : probe128_end(v.hs3, qac))) return 0;
       const uint32_t mv =
-          hm ? uint32_t(in_short(sh->mem + kB4AdjAt + (2 - uint32_t(slot)) * kB4ShortAdj,
-                                 slot == 0 ? sh->n_c : (slot == 1 ? sh->n_b : sh->n_a), y))
+          hm ? uint32_t(in_short(sh.mem + kB4AdjAt + (2 - uint32_t(slot)) * kB4ShortAdj,
+                                 slot == 0 ? sh.n_c : (slot == 1 ? sh.n_b : sh.n_a), y))
              : (rm >= 0 ? hub_adj(pl, rm, y) : uint32_t(probe64_end(v.hs2, pm)));
       const uint32_t lo = pair_adj & 1u, hi = pair_adj >> 1;
       const uint32_t av = slot == 2 ? mv : lo;
@@ -375,36 +385,36 @@ __device__ __forceinline__ uint32_t b4_exception(const View& v, const PairLinks&
   }
   // y's pairs with the two members of the slot's pair come with the entry
   Probe64 pa, pb, pc;
-  if ((slot == 2 || slot == 3) && !ha && x.ra < 0) pa = probe2_start(v.hs2, a, y);
-  if ((slot == 1 || slot == 3) && !hb && x.rb < 0) pb = probe2_start(v.hs2, b, y);
-  if ((slot == 0 || slot == 3) && !hc && x.rc < 0) pc = probe2_start(v.hs2, c, y);
+  if ((slot == 2 || slot == 3) && !ha && ra < 0) pa = probe2_start(v.hs2, a, y);
+  if ((slot == 1 || slot == 3) && !hb && rb < 0) pb = probe2_start(v.hs2, b, y);
+  if ((slot == 0 || slot == 3) && !hc && rc < 0) pc = probe2_start(v.hs2, c, y);
   const uint32_t abv =
-      slot == 0 ? 1u : uint32_t(hab ? in_short(sh->mem, sh->n_ab, y) : probe128_end(v.hs3, pab));
+      slot == 0 ? 1u : uint32_t(hab ? in_short(sh.mem, sh.n_ab, y) : probe128_end(v.hs3, pab));
   const uint32_t acv =
-      slot == 1 ? 1u : uint32_t(hac ? in_short(sh->mem + kB4ShortRun, sh->n_ac, y) : probe128_end(v.hs3, pac));
+      slot == 1 ? 1u : uint32_t(hac ? in_short(sh.mem + kB4ShortRun, sh.n_ac, y) : probe128_end(v.hs3, pac));
   const uint32_t bcv =
-      slot == 2 ? 1u : uint32_t(hbc ? in_short(sh->mem + 2 * kB4ShortRun, sh->n_bc, y) : probe128_end(v.hs3, pbc));
+      slot == 2 ? 1u : uint32_t(hbc ? in_short(sh.mem + 2 * kB4ShortRun, sh.n_bc, y) : probe128_end(v.hs3, pbc));
   // each exceptional node once: a 3-node hyperedge of an earlier slot takes it
   if (slot == 1 && abv) return 0;
   if (slot == 2 && (abv || acv)) return 0;
   if (slot == 3 && (abv || acv || bcv)) return 0;
   const uint32_t quad =
-      slot == 3 ? 1u : uint32_t(hq ? in_short(sh->mem + kB4QAt, sh->n_q, y) : probe128_end(v.hs4, pq));
+      slot == 3 ? 1u : uint32_t(hq ? in_short(sh.mem + kB4QAt, sh.n_q, y) : probe128_end(v.hs4, pq));
   const uint32_t av =
       slot == 0 || slot == 1
           ? (pair_adj & 1u)
-          : (ha ? uint32_t(in_short(sh->mem + kB4AdjAt, sh->n_a, y))
-                : (x.ra >= 0 ? hub_adj(pl, x.ra, y) : uint32_t(probe64_end(v.hs2, pa))));
+          : (ha ? uint32_t(in_short(sh.mem + kB4AdjAt, sh.n_a, y))
+                : (ra >= 0 ? hub_adj(pl, ra, y) : uint32_t(probe64_end(v.hs2, pa))));
   const uint32_t bv =
       slot == 0 ? (pair_adj >> 1)
                 : (slot == 2 ? (pair_adj & 1u)
-                             : (hb ? uint32_t(in_short(sh->mem + kB4AdjAt + kB4ShortAdj, sh->n_b, y))
-                                   : (x.rb >= 0 ? hub_adj(pl, x.rb, y) : uint32_t(probe64_end(v.hs2, pb)))));
+                             : (hb ? uint32_t(in_short(sh.mem + kB4AdjAt + kB4ShortAdj, sh.n_b, y))
+                                   : (rb >= 0 ? hub_adj(pl, rb, y) : uint32_t(probe64_end(v.hs2, pb)))));
   const uint32_t cv =
       slot == 1 || slot == 2
           ? (pair_adj >> 1)
-          : (hc ? uint32_t(in_short(sh->mem + kB4AdjAt + 2 * kB4ShortAdj, sh->n_c, y))
-                : (x.rc >= 0 ? hub_adj(pl, x.rc, y) : uint32_t(probe64_end(v.hs2, pc))));
+          : (hc ? uint32_t(in_short(sh.mem + kB4AdjAt + 2 * kB4ShortAdj, sh.n_c, y))
+                : (rc >= 0 ? hub_adj(pl, rc, y) : uint32_t(probe64_end(v.hs2, pc))));
   const uint32_t combo = av | (bv << 1) | (cv << 2);
   bool counted = !quad;   // a 4-node hyperedge: counted on its own, or larger than a sampled 3-node one
   if (OWN && counted) {
@@ -434,14 +444,13 @@ __device__ void b4_sparse(const View& v, const PairLinks& pl, uint32_t a, uint32
   const B4Ctx x = b4_ctx(v, pl, a, b, c);
   uint32_t n[8];
   b4_combo_counts(v, pl, x, n);
-  B4Short sh;
-  if (short_mem) sh = b4_short(v, pl, x, short_mem);
+  const B4Short sh = short_mem ? b4_short(v, pl, x, short_mem) : b4_short_none();
   // exceptional nodes, in one lane-strided range; per lane, the number of
   // them in each pairwise combination
   uint32_t dn1 = 0, dn2 = 0, dn3 = 0, dn4 = 0, dn5 = 0, dn6 = 0, dn7 = 0;
   for (uint64_t t = lane; t < x.total; t += kWave) {
     uint32_t pat;
-    const uint32_t r = b4_exception<OWN>(v, pl, x, t, &pat, short_mem ? &sh : nullptr);
+    const uint32_t r = b4_exception<OWN>(v, pl, x, t, &pat, sh);
     if (!r) continue;
     const uint32_t combo = r & 7u;
     dn1 += combo == 1;

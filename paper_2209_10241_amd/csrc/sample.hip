@@ -125,7 +125,7 @@ __device__ __forceinline__ void j3_exceptions(const View& v, const PairLinks& pl
                                      unsigned long long* h) {
   for (uint64_t t = first + lane; t < last; t += stride) {
     uint32_t pat;
-    const uint32_t r = b4_exception<false>(v, pl, x, t, &pat);
+    const uint32_t r = b4_exception<false>(v, pl, x, t, &pat, b4_short_none());
     if (!r) continue;
     if (r & 7u) {
       const uint8_t cc = lut[b4_combo_pattern(x, r & 7u)];
