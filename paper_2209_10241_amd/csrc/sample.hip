@@ -213,9 +213,10 @@ struct NodeStats {
 //   in N(s) u T or {s, y, z} is a 3-node hyperedge; the 4-node hyperedges
 //   holding e one by one.
 // One workgroup per sample; the walks over T and over the corrections go to
-// the work queue when longer than one chunk.
+// the work queue in chunks.
 struct J2SparseLds {
   uint32_t tcls[4];
+  uint32_t tlo[4];   // nodes of T below s, by class
   // flat walks over up to 256 items, each with up to three row segments
   uint32_t pre[kThreads + 1];
   uint32_t wave_tot[kWavesPerBlock];
@@ -557,10 +558,46 @@ __device__ void sample_j2_k4_sparse(const View& v, const PairLinks& pl, const No
     const J2Ctx c = j2_ctx(v, pl, es, d.n[2], i);
     const uint32_t s = c.s, o = c.o, ds = c.ds, dO = c.dO;
     const uint32_t n_t = uint32_t(c.thi - c.tlo);
-    if (tid < 4) L.tcls[tid] = 0;
+    if (tid < 4) {
+      L.tcls[tid] = 0;
+      L.tlo[tid] = 0;
+    }
     __syncthreads();
-    // class sizes of T
-    for (uint64_t p = c.tlo + tid; p < c.thi; p += kThreads) atomicAdd(&L.tcls[j2_t_cls(pl, c, p)], 1u);
+    // one pass over T: its class sizes, and how many of each class lie below
+    // s (for the corrections {s, o, t} below), counted per thread and summed
+    // per wavefront before they reach LDS
+    {
+      uint32_t k0 = 0, k1 = 0, k2 = 0, k3 = 0, b0 = 0, b1 = 0, b2 = 0, b3 = 0;
+      for (uint64_t p = c.tlo + tid; p < c.thi; p += kThreads) {
+        const uint32_t cls = j2_t_cls(pl, c, p), lo = j2_t_node(v, pl, c, p) < s;
+        k0 += cls == 0;
+        k1 += cls == 1;
+        k2 += cls == 2;
+        k3 += cls == 3;
+        b0 += lo & (cls == 0);
+        b1 += lo & (cls == 1);
+        b2 += lo & (cls == 2);
+        b3 += lo & (cls == 3);
+      }
+      k0 = wave_sum_u32(k0);
+      k1 = wave_sum_u32(k1);
+      k2 = wave_sum_u32(k2);
+      k3 = wave_sum_u32(k3);
+      b0 = wave_sum_u32(b0);
+      b1 = wave_sum_u32(b1);
+      b2 = wave_sum_u32(b2);
+      b3 = wave_sum_u32(b3);
+      if ((tid & (kWave - 1)) == 0) {
+        atomicAdd(&L.tcls[0], k0);
+        atomicAdd(&L.tcls[1], k1);
+        atomicAdd(&L.tcls[2], k2);
+        atomicAdd(&L.tcls[3], k3);
+        atomicAdd(&L.tlo[0], b0);
+        atomicAdd(&L.tlo[1], b1);
+        atomicAdd(&L.tlo[2], b2);
+        atomicAdd(&L.tlo[3], b3);
+      }
+    }
     __syncthreads();
     const uint32_t tc1 = L.tcls[1], tc2 = L.tcls[2], tc3 = L.tcls[3];
     // ---- first term (all of A), less every pair inside T as if not joined
@@ -599,18 +636,25 @@ __device__ void sample_j2_k4_sparse(const View& v, const PairLinks& pl, const No
       const uint32_t bb = tid;
       hsub(lut, h, 1u | ((bb & 1u) << 2) | (((bb >> 1) & 1u) << 5) | ((bb >> 2) << 7), ns.h3[8ull * o + bb]);
     }
-    // corrections: the hyperedges {s, o, t}
-    for (uint64_t p = c.tlo + tid; p < c.thi; p += kThreads)
-      hadd(lut, h, j2_agg_pat_t(c, j2_t_node(v, pl, c, p), j2_t_cls(pl, c, p)), 1);
+    // corrections: the hyperedges {s, o, t}, by the class of t and its side of s
+    if (tid < 8) {
+      const uint32_t cls = tid & 3u, below_s = tid >> 2;
+      const uint32_t n = below_s ? L.tlo[cls] : L.tcls[cls] - L.tlo[cls];
+      hadd(lut, h, j2_agg_pat_t(c, below_s ? 0u : 0xFFFFFFFFu, cls), n);
+    }
     // ---- the walks over T and over the corrections, and the hyperedges at s
-    // and holding e: here when short, else queued
+    // and holding e: queued in chunks (here only without a queue, or when it
+    // is full)
     const uint32_t n_r = ds + n_t;
     const uint32_t n_s = v.i3_off[s + 1] - v.i3_off[s];
     const uint32_t qn = j2_q_node(v, c), n_q = v.i4_off[qn + 1] - v.i4_off[qn];
     const uint32_t jobs_t = (n_t + q.ct - 1) / q.ct, jobs_r = (n_r + q.cr - 1) / q.cr;
     const uint32_t jobs_s = (n_s + q.ch - 1) / q.ch, jobs_q = (n_q + q.ch - 1) / q.ch;
     const uint32_t jobs = jobs_t + jobs_r + jobs_s + jobs_q;
-    bool here = q.job == nullptr || (jobs_t <= 1 && jobs_r <= 1 && jobs_s <= 1 && jobs_q <= 1);
+    // every walk goes to the queue when there is one: a walk's cost follows
+    // the runs it meets, not its item count, and the drain's claiming
+    // balances them
+    bool here = q.job == nullptr;
     if (!here) {
       if (tid == 0) {
         q_base = queue_reserve(q, jobs);
