@@ -89,13 +89,13 @@ __device__ void sample_j4(const View& v, const Draws& d, uint32_t part, uint32_t
 // workgroup of a second launch so that one sample's work spreads over many.
 enum : uint32_t { kJobNone = 0, kJobPairT = 1, kJobPairR = 2, kJobTriple = 3, kJobPairS = 4, kJobPairQ = 5 };
 // default chunk sizes (divided by the HM_OPT_SAMPLE_CHUNK_SCALE option)
-constexpr uint32_t kChunkT = 4;    // nodes of T per chunk
-constexpr uint32_t kChunkR = 16;   // correction items per chunk
+constexpr uint32_t kChunkT = 2;    // nodes of T per chunk
+constexpr uint32_t kChunkR = 4;    // correction items per chunk
 constexpr uint32_t kChunkX = 128;  // exception positions per chunk
 constexpr uint32_t kChunkH = 256;  // hyperedges at s (3-node) or holding e (4-node) per chunk
 // queue entries per sample of strata 2 and 3 (times the chunk option), at
 // most kQueueMax in all; work that finds the queue full is done in place
-constexpr uint64_t kQueuePerSample = 512;
+constexpr uint64_t kQueuePerSample = 2048;
 constexpr uint64_t kQueueMax = 1ull << 26;
 
 struct Queue {
