@@ -295,8 +295,10 @@ int count_sampled_weighted_indices(const hm_graph* H, int k, const uint32_t* idx
  *   HM_OPT_SAMPLE_CHUNK_SCALE the sampled counts of graphs without bit rows
  *                            hand the long walks of heavy samples to a work
  *                            queue in chunks (2 nodes of T, 4 correction
- *                            items, 128 exception positions, 256 hyperedges);
- *                            every chunk size is divided by this value
+ *                            items, 128 exception positions, 256 hyperedges;
+ *                            pair samples with a bound above 4096 visited
+ *                            positions); every chunk size and that bound
+ *                            are divided by this value
  *                            (default 1, range 1..1024), so larger values
  *                            route more of the work through the queue.  The
  *                            results do not depend on it.

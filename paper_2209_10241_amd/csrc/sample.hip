@@ -96,6 +96,9 @@ constexpr uint32_t kChunkH = 256;  // hyperedges at s (3-node) or holding e (4-n
 // queue entries per sample of strata 2 and 3 (times the chunk option), at
 // most kQueueMax in all; work that finds the queue full is done in place
 constexpr uint64_t kQueuePerSample = 2048;
+// pair samples whose walks visit at most about this many positions walk them
+// in place (divided by the HM_OPT_SAMPLE_CHUNK_SCALE option)
+constexpr uint64_t kInlineWork = 4096;
 constexpr uint64_t kQueueMax = 1ull << 26;
 
 struct Queue {
@@ -105,6 +108,7 @@ struct Queue {
   unsigned long long* head;     // claimed entries
   uint32_t* tcls;               // per pair sample: |T n A_q|, q = 1..3
   uint32_t ct, cr, cx, ch;      // chunk sizes: nodes of T, correction items, exception positions, hyperedges
+  uint64_t inline_work;         // pair samples with a smaller bound on visited positions walk in place
 };
 
 // Reserve n entries; returns the first, or ~0 when they do not fit (the
@@ -212,8 +216,8 @@ struct NodeStats {
 //   corrected one by one for the 3-node hyperedges {o, y, z} where y or z is
 //   in N(s) u T or {s, y, z} is a 3-node hyperedge; the 4-node hyperedges
 //   holding e one by one.
-// One workgroup per sample; the walks over T and over the corrections go to
-// the work queue in chunks.
+// One workgroup per sample; the walks over T and over the corrections of a
+// heavy sample go to the work queue in chunks.
 struct J2SparseLds {
   uint32_t tcls[4];
   uint32_t tlo[4];   // nodes of T below s, by class
@@ -643,18 +647,20 @@ __device__ void sample_j2_k4_sparse(const View& v, const PairLinks& pl, const No
       hadd(lut, h, j2_agg_pat_t(c, below_s ? 0u : 0xFFFFFFFFu, cls), n);
     }
     // ---- the walks over T and over the corrections, and the hyperedges at s
-    // and holding e: queued in chunks (here only without a queue, or when it
-    // is full)
+    // and holding e: here when light, else queued in chunks
     const uint32_t n_r = ds + n_t;
     const uint32_t n_s = v.i3_off[s + 1] - v.i3_off[s];
     const uint32_t qn = j2_q_node(v, c), n_q = v.i4_off[qn + 1] - v.i4_off[qn];
     const uint32_t jobs_t = (n_t + q.ct - 1) / q.ct, jobs_r = (n_r + q.cr - 1) / q.cr;
     const uint32_t jobs_s = (n_s + q.ch - 1) / q.ch, jobs_q = (n_q + q.ch - 1) / q.ch;
     const uint32_t jobs = jobs_t + jobs_r + jobs_s + jobs_q;
-    // every walk goes to the queue when there is one: a walk's cost follows
-    // the runs it meets, not its item count, and the drain's claiming
+    // the walks stay here only when a bound on the positions they visit is
+    // small (the correction walk meets at most one run of 3-node hyperedges
+    // at o per item); otherwise they go to the queue, whose claiming
     // balances them
-    bool here = q.job == nullptr;
+    const uint64_t work_bound = uint64_t(n_r) * (v.i3_off[o + 1] - v.i3_off[o]) +
+                                uint64_t(n_t) * (uint64_t(ds) + dO + n_t) + n_s + n_q;
+    bool here = q.job == nullptr || work_bound <= q.inline_work;
     if (!here) {
       if (tid == 0) {
         q_base = queue_reserve(q, jobs);
@@ -1191,6 +1197,7 @@ int launch_sampled(const hm_graph* H, int k, const uint32_t* const idx[5], const
   a.q.cr = std::max<uint32_t>(1, kChunkR / scale);
   a.q.cx = std::max<uint32_t>(1, kChunkX / scale);
   a.q.ch = std::max<uint32_t>(1, kChunkH / scale);
+  a.q.inline_work = kInlineWork / scale;
   struct Release {
     void* p[2] = {nullptr, nullptr};
     ~Release() {
