@@ -851,8 +851,8 @@ int count_sparse(const hm_graph* H, int k, hipStream_t st) {
   cls.clique = t.lut4[kPairBits4];
   if (k == 4 && n2) {
     // 4-cycles
-    // workgroups, each with 8 bytes of counters per node: at most about 1 GiB
-    const unsigned g = grid_cap(H->n_nodes, 1, unsigned(std::max<uint64_t>(64, std::min<uint64_t>(512, (1ull << 27) / std::max<uint32_t>(H->n_nodes, 1)))));
+    // workgroups, each with 8 bytes of counters per node: at most about 2 GiB
+    const unsigned g = grid_cap(H->n_nodes, 1, unsigned(std::max<uint64_t>(64, std::min<uint64_t>(1024, (1ull << 28) / std::max<uint32_t>(H->n_nodes, 1)))));
     uint32_t *cnt = nullptr, *touched = nullptr;
     HM_TRY(tmp.get(&cnt, uint64_t(g) * H->n_nodes));
     HM_TRY(tmp.get(&touched, uint64_t(g) * H->n_nodes));
