@@ -265,7 +265,7 @@ def large_workloads(hm, W, torch, seeds: int = 32, exact_only: bool = False) -> 
         torch.cuda.synchronize()
         first_learned_ms = (time.perf_counter() - t0) * 1e3
         rows = {}
-        for f in (0.0025, 0.005, 0.01, 0.02):
+        for f in (0.0007, 0.001, 0.0015, 0.0025, 0.005, 0.01, 0.02):
             ms_u, ru = timed(lambda i: hm.count_sampled(g, 4, f, 1000 + i, stream=stream)[0], seeds)
             ms_l, rl = timed(lambda i: hm.count_sampled_learned(g, model, 4, f, 1000 + i, stream=stream)[0], seeds)
             rows[f"{f:g}"] = {

@@ -437,7 +437,7 @@ class Model:
         self.close()
 
 
-def hm_model_train(H: Graph, k: int, epochs: int = 30, batch: int = 4096, lr: float = 3e-3, gamma: float = 0.5,
+def hm_model_train(H: Graph, k: int, epochs: int = 30, batch: int = 4096, lr: float = 3e-3, gamma: float = 0.7,
                    epsilon: float = 0.1, seed: int = 0) -> Model:
     opts = TrainOpts(epochs, batch, lr, gamma, epsilon, int(seed) & (2**64 - 1))
     out = ctypes.c_void_p()
