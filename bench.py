@@ -315,7 +315,7 @@ def main() -> int:
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the counting path runs on a single MI355X "
-              "(multi-GPU sharding is described in DESIGN.md but not built)", file=sys.stderr)
+              "(sharding across GPUs is designed but not built)", file=sys.stderr)
         return 2
 
     import torch
