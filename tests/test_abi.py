@@ -52,3 +52,33 @@ def test_host_errors():
         hm.hm_class_info(4, 171)
     with pytest.raises(hm.HMError):
         hm.hm_pattern_class(4, 2048)
+
+
+def test_options_host_logic():
+    """Options are process-wide host settings: values in range are kept, values
+    out of range and unknown options are refused (no GPU call)."""
+    import paper_2209_10241_amd as hm
+    cases = [(hm.HM_OPT_BITSET_MAX_NODES, 8192, [-1, 8193]),
+             (hm.HM_OPT_SAMPLE_CHUNK_SCALE, 1, [0, 1025]),
+             (hm.HM_OPT_ONE_PASS_MAX_EDGES, 1 << 20, [-1, (1 << 20) + 1]),
+             (hm.HM_OPT_HUB_MIN_DEGREE, 256, [-1, 1 << 32])]
+    for opt, default, bad in cases:
+        assert hm.hm_get_option(opt) == default
+        for b in bad:
+            with pytest.raises(hm.HMError):
+                hm.hm_set_option(opt, b)
+        assert hm.hm_get_option(opt) == default
+        hm.hm_set_option(opt, default - 1 if default > 1 else default + 1)
+        assert hm.hm_get_option(opt) == (default - 1 if default > 1 else default + 1)
+        hm.hm_set_option(opt, default)
+    with pytest.raises(hm.HMError):
+        hm.hm_set_option(99, 1)
+
+
+def test_bench_refuses_several_gpus():
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True, text=True,
+                       timeout=120)
+    assert r.returncode == 2 and "one GPU" in r.stderr
