@@ -29,6 +29,9 @@ def lib():
         i64 = ctypes.c_int64
         _lib.oracle_count_exact.argtypes = [ctypes.c_int, ctypes.c_uint32, u32p, i64, u32p, i64, u32p, i64, i64p]
         _lib.oracle_count_exact.restype = ctypes.c_int
+        _lib.oracle_count_baseline.argtypes = [ctypes.c_int, ctypes.c_uint32, u32p, i64p, i64, u32p, i64, u32p, i64,
+                                               u32p, i64, i64p, i64p]
+        _lib.oracle_count_baseline.restype = ctypes.c_int
         _lib.oracle_sampled_raw.argtypes = [ctypes.c_int, ctypes.c_uint32, u32p, i64, u32p, i64, u32p, i64,
                                             i64p, i64, i64p, i64, i64p, i64, i64p]
         _lib.oracle_sampled_raw.restype = ctypes.c_int
@@ -101,6 +104,23 @@ def count_exact(h, k: int) -> np.ndarray:
     if rc != 0:
         raise RuntimeError("oracle_count_exact failed")
     return out
+
+
+def count_baseline(h, k: int):
+    """Exact counts by the baseline of Section 4.1 (Algorithm 1): ESU on the
+    clique projection of every hyperedge, keeping the candidates whose induced
+    sub-hypergraph is connected.  Returns (counts, candidates, discarded)."""
+    nh = h if isinstance(h, Normalised) else normalise(h)
+    members = np.ascontiguousarray([v for e in nh.order for v in e], dtype=np.uint32)
+    offsets = np.zeros(len(nh.order) + 1, dtype=np.int64)
+    offsets[1:] = np.cumsum([len(e) for e in nh.order], dtype=np.int64)
+    out = np.zeros(table(k).n_classes, dtype=np.int64)
+    stats = np.zeros(2, dtype=np.int64)
+    rc = lib().oracle_count_baseline(k, nh.n_nodes, members, offsets, len(nh.order), _flat(nh, 2), nh.count(2),
+                                     _flat(nh, 3), nh.count(3), _flat(nh, 4), nh.count(4), out, stats)
+    if rc != 0:
+        raise RuntimeError("oracle_count_baseline failed")
+    return out, int(stats[0]), int(stats[1])
 
 
 def sampled_raw(h, k: int, samples: dict) -> np.ndarray:

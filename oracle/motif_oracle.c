@@ -17,7 +17,9 @@
  *     "visited" set of Algorithms 2 and 3
  *   - fill-in of a node set and its isomorphism class (Section 4.3)
  *   - ESU (Wernicke 2006), used by Algorithms 2 and 3 on the pairwise graph
+ *     and by Algorithm 1 on the clique projection
  *   - Algorithm 2 (order 3) and Algorithm 3 (order 4), exact
+ *   - Algorithm 1 (the baseline of Section 4.1), exact
  *   - Algorithm 4, sampled, on an explicit list of sampled hyperedges
  */
 #include <stdint.h>
@@ -358,10 +360,11 @@ static uint32_t fill_in(const hgraph *g, const uint32_t *V, int k)
     return p;
 }
 
-static int g2_adjacent(const hgraph *g, uint32_t a, uint32_t b)
+/* b in the ascending neighbour row of a (graph given as off/adj) */
+static int row_adjacent(const int64_t *off, const uint32_t *adj, uint32_t a, uint32_t b)
 {
-    const uint32_t *row = g->g2_adj + g->g2_off[a];
-    size_t n = (size_t)(g->g2_off[a + 1] - g->g2_off[a]);
+    const uint32_t *row = adj + off[a];
+    size_t n = (size_t)(off[a + 1] - off[a]);
     return bsearch(&b, row, n, sizeof(uint32_t), cmp_u32) != NULL;
 }
 
@@ -376,11 +379,13 @@ static void sort_nodes(uint32_t *V, int n)
 }
 
 /* ------------------------------------------------------------------ */
-/* ESU (Wernicke 2006) on the pairwise graph: each connected k-node set  */
-/* is produced exactly once, from its smallest node.                   */
+/* ESU (Wernicke 2006) on a graph given as ascending neighbour rows:   */
+/* each connected k-node set is produced exactly once, from its        */
+/* smallest node.                                                      */
 /* ------------------------------------------------------------------ */
 typedef struct {
-    const hgraph *g;
+    const int64_t *off;
+    const uint32_t *adj;
     int k;
     void (*emit)(void *ctx, const uint32_t *V);
     void *ctx;
@@ -407,18 +412,18 @@ static void esu_extend(esu_ctx *c, uint32_t *Vsub, int nsub, const uint32_t *Vex
             esu_extend(c, Vsub, nsub + 1, ext, 0, root);
             continue;
         }
-        int64_t deg = c->g->g2_off[w + 1] - c->g->g2_off[w];
+        int64_t deg = c->off[w + 1] - c->off[w];
         uint32_t *ext2 = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)(next + deg + 1));
         if (!ext2) { c->failed = 1; break; }
         memcpy(ext2, ext, sizeof(uint32_t) * (size_t)next);
         int64_t n2 = next;
         /* exclusive neighbours of w: not in Vsub and not adjacent to Vsub */
         for (int64_t i = 0; i < deg; i++) {
-            uint32_t u = c->g->g2_adj[c->g->g2_off[w] + i];
+            uint32_t u = c->adj[c->off[w] + i];
             if (u <= root) continue;
             int excl = 1;
             for (int s = 0; s < nsub && excl; s++)
-                if (Vsub[s] == u || g2_adjacent(c->g, Vsub[s], u)) excl = 0;
+                if (Vsub[s] == u || row_adjacent(c->off, c->adj, Vsub[s], u)) excl = 0;
             if (excl) ext2[n2++] = u;
         }
         Vsub[nsub] = w;
@@ -428,16 +433,17 @@ static void esu_extend(esu_ctx *c, uint32_t *Vsub, int nsub, const uint32_t *Vex
     free(ext);
 }
 
-static void esu(const hgraph *g, int k, void (*emit)(void *, const uint32_t *), void *ctx, int *failed)
+static void esu(const int64_t *off, const uint32_t *adj, uint32_t n_nodes, int k,
+                void (*emit)(void *, const uint32_t *), void *ctx, int *failed)
 {
-    esu_ctx c = { g, k, emit, ctx, 0 };
-    for (uint32_t v = 0; v < g->n_nodes && !c.failed; v++) {
-        int64_t deg = g->g2_off[v + 1] - g->g2_off[v];
+    esu_ctx c = { off, adj, k, emit, ctx, 0 };
+    for (uint32_t v = 0; v < n_nodes && !c.failed; v++) {
+        int64_t deg = off[v + 1] - off[v];
         uint32_t *ext = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)(deg + 1));
         if (!ext) { c.failed = 1; break; }
         int64_t n = 0;
         for (int64_t i = 0; i < deg; i++) {
-            uint32_t u = g->g2_adj[g->g2_off[v] + i];
+            uint32_t u = adj[off[v] + i];
             if (u > v) ext[n++] = u;
         }
         uint32_t Vsub[4] = { v, 0, 0, 0 };
@@ -539,13 +545,101 @@ int oracle_count_exact(int k, uint32_t n_nodes,
     if (!failed) {
         exact_ctx c = { &g, k, &visited, M, 0 };
         int esu_failed = 0;
-        esu(&g, k, exact_emit_unvisited, &c, &esu_failed);
+        esu(g.g2_off, g.g2_adj, g.n_nodes, k, exact_emit_unvisited, &c, &esu_failed);
         failed = c.failed || esu_failed;
     }
     tupset_free(&visited);
     hgraph_free(&g);
     if (failed) return -1;
     memcpy(counts, M, sizeof(int64_t) * (size_t)n_class[k]);
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* Algorithm 1: the baseline of Section 4.1.                           */
+/* ------------------------------------------------------------------ */
+typedef struct {
+    const hgraph *g;
+    int k;
+    int64_t *M;
+    int64_t candidates, discarded;
+} base_ctx;
+
+/* a connected k-node set of the projection: count it when the
+ * sub-hypergraph it induces is connected, else discard it */
+static void base_emit(void *p, const uint32_t *V)
+{
+    base_ctx *c = (base_ctx *)p;
+    c->candidates++;
+    int cls = pattern_class(fill_in(c->g, V, c->k), c->k);
+    if (cls < 0) { c->discarded++; return; }
+    c->M[cls]++;
+}
+
+/* Count every order-k motif (k = 3 or 4) the way the baseline does: build the
+ * projection G of the hypergraph (every hyperedge of size >= 2, whatever its
+ * size, replaced by a clique), enumerate the connected k-node sets of G with
+ * ESU, and keep those whose induced sub-hypergraph is connected.  members /
+ * offsets hold every unique hyperedge of size >= 2 (n_all of them); e2..e4 the
+ * unique hyperedges of sizes 2..k, for fill-in.  stats[0] receives the number
+ * of candidates ESU produced, stats[1] the number discarded.  Returns 0 on
+ * success, -1 on bad arguments or allocation failure. */
+int oracle_count_baseline(int k, uint32_t n_nodes, const uint32_t *members, const int64_t *offsets, int64_t n_all,
+                          const uint32_t *e2, int64_t n2, const uint32_t *e3, int64_t n3,
+                          const uint32_t *e4, int64_t n4, int64_t *counts, int64_t *stats)
+{
+    if (k != 3 && k != 4) return -1;
+    build_tables();
+    hgraph g;
+    if (hgraph_build(&g, k, n_nodes, e2, n2, e3, n3, e4, n4) != 0) { hgraph_free(&g); return -1; }
+    /* the projection: every ordered pair of distinct members of every
+     * hyperedge, then each row sorted and its repeats dropped */
+    int64_t n_pairs = 0;
+    for (int64_t i = 0; i < n_all; i++) {
+        int64_t s = offsets[i + 1] - offsets[i];
+        n_pairs += s * (s - 1);
+    }
+    int64_t *off = (int64_t *)calloc((size_t)n_nodes + 1, sizeof(int64_t));
+    int64_t *fill = (int64_t *)malloc(((size_t)n_nodes + 1) * sizeof(int64_t));
+    uint32_t *adj = (uint32_t *)malloc((size_t)(n_pairs + 1) * sizeof(uint32_t));
+    int failed = !off || !fill || !adj;
+    if (!failed) {
+        for (int64_t i = 0; i < n_all; i++)
+            for (int64_t x = offsets[i]; x < offsets[i + 1]; x++)
+                off[members[x] + 1] += offsets[i + 1] - offsets[i] - 1;
+        for (uint32_t v = 0; v < n_nodes; v++) off[v + 1] += off[v];
+        memcpy(fill, off, ((size_t)n_nodes + 1) * sizeof(int64_t));
+        for (int64_t i = 0; i < n_all; i++)
+            for (int64_t x = offsets[i]; x < offsets[i + 1]; x++)
+                for (int64_t y = offsets[i]; y < offsets[i + 1]; y++)
+                    if (x != y) adj[fill[members[x]]++] = members[y];
+        /* compact: row v keeps its distinct neighbours, ascending */
+        int64_t w = 0, start = 0;
+        for (uint32_t v = 0; v < n_nodes; v++) {
+            int64_t end = off[v + 1];
+            qsort(adj + start, (size_t)(end - start), sizeof(uint32_t), cmp_u32);
+            int64_t row = w;
+            for (int64_t x = start; x < end; x++)
+                if (x == start || adj[x] != adj[x - 1]) adj[w++] = adj[x];
+            off[v] = row;
+            start = end;
+        }
+        off[n_nodes] = w;
+    }
+    int64_t M[256];
+    memset(M, 0, sizeof(M));
+    base_ctx c = { &g, k, M, 0, 0 };
+    if (!failed) {
+        int esu_failed = 0;
+        esu(off, adj, n_nodes, k, base_emit, &c, &esu_failed);
+        failed = esu_failed;
+    }
+    free(off); free(fill); free(adj);
+    hgraph_free(&g);
+    if (failed) return -1;
+    memcpy(counts, M, sizeof(int64_t) * (size_t)n_class[k]);
+    stats[0] = c.candidates;
+    stats[1] = c.discarded;
     return 0;
 }
 
