@@ -131,6 +131,25 @@ int hm_graph_export(const hm_graph* H, int j, uint32_t* out);
  * overwritten.  Asynchronous on `stream`. */
 int count_exact(const hm_graph* H, int k, int64_t* counts, void* stream);
 
+/* Exact counts of every order-k motif (k = 3 or 4) by the baseline of
+ * Section 4.1 (Algorithm 1): the clique projection G of the hypergraph (two
+ * nodes joined when a hyperedge of any size >= 2 holds both), every connected
+ * k-node set of G enumerated once by ESU, and each kept when the
+ * sub-hypergraph it induces is connected.  The counts equal count_exact's;
+ * the path exists to measure what the hyperedge-based generators save.
+ * counts: device int64 array of hm_num_classes(k) values, overwritten.
+ * stats: device uint64 array of 2 values, overwritten: the candidates ESU
+ * produced, and those discarded (induced sub-hypergraph not connected).
+ * The first call allocates the projection's bit rows (n_nodes * ceil(n_nodes
+ * / 32) words, kept with the graph); every call rebuilds them.  Asynchronous
+ * on `stream`; calls on one graph are serialised by the caller, as for
+ * count_exact.
+ * Errors: HM_EINVAL for a NULL argument; HM_EUNSUPPORTED for k other than 3
+ * or 4, or for a graph without adjacency bit rows (more nodes than
+ * HM_OPT_BITSET_MAX_NODES); HM_ENOMEM when the bit rows cannot be
+ * allocated. */
+int count_baseline(const hm_graph* H, int k, int64_t* counts, uint64_t* stats, void* stream);
+
 /* ---------------------------------------------------------------- sampled */
 
 /* Sample allocation over strata (Section 5: S_j draws from the hyperedges of

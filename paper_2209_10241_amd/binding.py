@@ -64,6 +64,7 @@ SIGNATURES = {
     "hm_graph_stats": (_int, [_vp, _vp]),
     "hm_graph_export": (_int, [_vp, _int, _vp]),
     "count_exact": (_int, [_vp, _int, _vp, _vp]),
+    "count_baseline": (_int, [_vp, _int, _vp, _vp, _vp]),
     "hm_sample_sizes": (_int, [_vp, _int, _dbl, _int, _vp]),
     "hm_sample_draw": (_int, [_vp, _int, _dbl, _u64, _int, _vp, _vp, _vp, _vp]),
     "count_sampled": (_int, [_vp, _int, _dbl, _u64, _int, _vp, _vp, _vp]),
@@ -228,6 +229,21 @@ def count_exact(H: Graph, k: int, out=None, stream=None):
         out = torch.empty(n, dtype=torch.int64, device="cuda")
     _check(lib().count_exact(H.handle, k, ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)))
     return out
+
+
+def count_baseline(H: Graph, k: int, out=None, stats=None, stream=None):
+    """Exact per-class counts by the projection baseline (Algorithm 1):
+    (int64 counts, uint64 [candidates, discarded]) torch tensors on the
+    current device."""
+    import torch
+    n = hm_num_classes(k)
+    if out is None:
+        out = torch.empty(n, dtype=torch.int64, device="cuda")
+    if stats is None:
+        stats = torch.empty(2, dtype=torch.int64, device="cuda")
+    _check(lib().count_baseline(H.handle, k, ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(stats.data_ptr()),
+                                _stream_ptr(stream)))
+    return out, stats
 
 
 def hm_profile_enable(on: bool = True) -> None:

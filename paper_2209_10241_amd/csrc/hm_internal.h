@@ -285,6 +285,9 @@ struct hm_graph {
   uint32_t* hub_bits = nullptr;
   uint32_t hub_words = 0;
   bool hub_built = false;
+  // bit rows of the clique projection (n_nodes x words), allocated by the
+  // first projection-baseline count and rewritten by every one
+  mutable uint32_t* proj_bits = nullptr;
   // per node, built on first use without bit rows: triangles at the node, sum
   // of its neighbours' degrees, its 3-node hyperedges by pairwise pattern (8)
   unsigned long long* ns_tri = nullptr;
