@@ -10,9 +10,9 @@
 // the point of this path is what it costs, not what it finds.
 //
 // Layout: G is kept as bit rows (n_nodes x W words, rebuilt by every call)
-// beside the graph's pairwise rows.  One wavefront takes a root r and one word
-// of r's row: for each first extension w1 > r in that word it forms ESU's
-// extension set of {r, w1} in LDS; at order 3 every member closes a
+// beside the graph's pairwise rows.  One wavefront takes a root r and a first
+// extension w1 > r joined to it, and forms ESU's extension set of {r, w1} in
+// LDS; at order 3 every member closes a
 // candidate, at order 4 the lanes share the second extensions w2 (by rank) and
 // each walks the third extension set of {r, w1, w2} word by word.
 #include <algorithm>
@@ -99,7 +99,9 @@ __device__ inline uint32_t base_pattern4(const View& v, const uint32_t* __restri
 }
 
 // ESU over G, counting per class in LDS (bin 0xFF: discarded candidates).
-// Items are (root r, word x of r's row); dynamic LDS holds W words per
+// Items are the ordered node pairs (r, w1), taken when w1 > r is joined to r
+// (ESU's first extension of root r); the waves stride over them, so the
+// heavy roots (small r) spread over the grid.  Dynamic LDS holds W words per
 // wavefront (the extension set of {r, w1}).
 template <int K>
 __global__ void __launch_bounds__(kBaseThreads) k_base_esu(View v, const uint32_t* __restrict__ P,
@@ -114,57 +116,53 @@ __global__ void __launch_bounds__(kBaseThreads) k_base_esu(View v, const uint32_
   const uint32_t N = v.N, W = v.W;
   const uint32_t wv = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
   uint32_t* ext = ext_lds + wv * W;
-  const uint64_t items = uint64_t(N) * W;
+  const uint64_t items = uint64_t(N) * N;
   const uint64_t n_waves = uint64_t(gridDim.x) * kBaseWaves;
   for (uint64_t it = uint64_t(blockIdx.x) * kBaseWaves + wv; it < items; it += n_waves) {
-    const uint32_t r = uint32_t(it / W), xw = uint32_t(it % W);
+    const uint32_t r = uint32_t(it / N), w1 = uint32_t(it % N);
     const uint32_t* Pr = P + uint64_t(r) * W;
-    uint32_t firsts = Pr[xw] & above(r, xw);
-    while (firsts) {
-      const uint32_t w1 = (xw << 5) | uint32_t(__ffs(firsts) - 1);
-      firsts &= firsts - 1;
-      const uint32_t* P1 = P + uint64_t(w1) * W;
-      // extension set of {r, w1}: r's neighbours after w1, and w1's
-      // neighbours above r that are not r's
-      for (uint32_t x = lane; x < W; x += kWave) ext[x] = (Pr[x] & above(w1, x)) | (P1[x] & ~Pr[x] & above(r, x));
-      wave_sync();
-      if (K == 3) {
-        for (uint32_t x = lane; x < W; x += kWave) {
-          uint32_t m = ext[x];
-          while (m) {
-            const uint32_t u = (x << 5) | uint32_t(__ffs(m) - 1);
-            m &= m - 1;
-            atomicAdd(&h_main[lut[base_pattern3(v, P, r, w1, u)]], 1ull);
-          }
+    if (w1 <= r || !((Pr[w1 >> 5] >> (w1 & 31)) & 1u)) continue;
+    const uint32_t* P1 = P + uint64_t(w1) * W;
+    // extension set of {r, w1}: r's neighbours after w1, and w1's
+    // neighbours above r that are not r's
+    for (uint32_t x = lane; x < W; x += kWave) ext[x] = (Pr[x] & above(w1, x)) | (P1[x] & ~Pr[x] & above(r, x));
+    wave_sync();
+    if (K == 3) {
+      for (uint32_t x = lane; x < W; x += kWave) {
+        uint32_t m = ext[x];
+        while (m) {
+          const uint32_t u = (x << 5) | uint32_t(__ffs(m) - 1);
+          m &= m - 1;
+          atomicAdd(&h_main[lut[base_pattern3(v, P, r, w1, u)]], 1ull);
         }
-      } else {
-        // second extensions by rank: a word holds at most 32, so each lane
-        // takes at most one per word
-        uint32_t rank = 0;
-        for (uint32_t x = 0; x < W; ++x) {
-          const uint32_t m = ext[x];
-          const uint32_t c = __popc(m);
-          const uint32_t j = (lane - rank) & (kWave - 1);
-          rank += c;
-          if (j >= c) continue;
-          uint32_t mm = m;
-          for (uint32_t q = 0; q < j; ++q) mm &= mm - 1;
-          const uint32_t w2 = (x << 5) | uint32_t(__ffs(mm) - 1);
-          const uint32_t* P2 = P + uint64_t(w2) * W;
-          // extension set of {r, w1, w2}: the set above after w2, and w2's
-          // neighbours above r joined to neither r nor w1
-          for (uint32_t y = 0; y < W; ++y) {
-            uint32_t e = (ext[y] & above(w2, y)) | (P2[y] & ~Pr[y] & ~P1[y] & above(r, y));
-            while (e) {
-              const uint32_t w3 = (y << 5) | uint32_t(__ffs(e) - 1);
-              e &= e - 1;
-              atomicAdd(&h_main[lut[base_pattern4(v, P, r, w1, w2, w3)]], 1ull);
-            }
+      }
+    } else {
+      // second extensions by rank: a word holds at most 32, so each lane
+      // takes at most one per word
+      uint32_t rank = 0;
+      for (uint32_t x = 0; x < W; ++x) {
+        const uint32_t m = ext[x];
+        const uint32_t c = __popc(m);
+        const uint32_t j = (lane - rank) & (kWave - 1);
+        rank += c;
+        if (j >= c) continue;
+        uint32_t mm = m;
+        for (uint32_t q = 0; q < j; ++q) mm &= mm - 1;
+        const uint32_t w2 = (x << 5) | uint32_t(__ffs(mm) - 1);
+        const uint32_t* P2 = P + uint64_t(w2) * W;
+        // extension set of {r, w1, w2}: the set above after w2, and w2's
+        // neighbours above r joined to neither r nor w1
+        for (uint32_t y = 0; y < W; ++y) {
+          uint32_t e = (ext[y] & above(w2, y)) | (P2[y] & ~Pr[y] & ~P1[y] & above(r, y));
+          while (e) {
+            const uint32_t w3 = (y << 5) | uint32_t(__ffs(e) - 1);
+            e &= e - 1;
+            atomicAdd(&h_main[lut[base_pattern4(v, P, r, w1, w2, w3)]], 1ull);
           }
         }
       }
-      wave_sync();   // ext is rewritten for the next w1
     }
+    wave_sync();   // ext is rewritten for the next item
   }
   __syncthreads();
   flush(h_main, hist_copy(hist, kExactHistStride) + kMain, 256);
@@ -224,7 +222,7 @@ int count_baseline_impl(const hm_graph* H, int k, int64_t* counts, unsigned long
   HM_HIP(hipGetLastError());
   const View v = view_of(H);
   const size_t lds = size_t(kBaseWaves) * H->words * sizeof(uint32_t);
-  const uint64_t items = words;
+  const uint64_t items = uint64_t(H->n_nodes) * H->n_nodes;
   const unsigned grid = unsigned(std::max<uint64_t>(1, std::min<uint64_t>(kBaseGrid, (items + kBaseWaves - 1) / kBaseWaves)));
   {
     ProfileScope ps("k_base_esu", st);
