@@ -38,9 +38,10 @@ def _golden(name, k):
     raise KeyError(name)
 
 
-# node counts spanning one to ten 32-bit words per row (ragged last word),
-# hyperedges of size 1 to 7 with repeats
-CASES = [(0, 20, 60), (1, 33, 90), (2, 64, 150), (3, 97, 220), (4, 150, 260), (5, 300, 400)]
+# node counts spanning one to ten 32-bit words per row (ragged last word)
+# and the largest graph kept as bit rows (8192 nodes, 256 words), hyperedges
+# of size 1 to 7 with repeats
+CASES = [(0, 20, 60), (1, 33, 90), (2, 64, 150), (3, 97, 220), (4, 150, 260), (5, 300, 400), (6, 8192, 6000)]
 
 
 @pytest.mark.parametrize("k", [3, 4])
