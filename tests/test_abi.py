@@ -18,7 +18,7 @@ def _declared():
 
 def test_header_declares_the_boundary():
     names = _declared()
-    for need in ("count_exact", "hm_graph_create", "hm_graph_destroy", "hm_num_classes"):
+    for need in ("count_exact", "count_baseline", "hm_graph_create", "hm_graph_destroy", "hm_num_classes"):
         assert need in names
 
 
@@ -52,6 +52,17 @@ def test_host_errors():
         hm.hm_class_info(4, 171)
     with pytest.raises(hm.HMError):
         hm.hm_pattern_class(4, 2048)
+
+
+def test_null_arguments_are_refused_before_the_device():
+    # argument checks run on the host and return before any HIP call
+    import ctypes
+    import paper_2209_10241_amd as hm
+    lib = hm.lib()
+    buf = (ctypes.c_uint64 * 256)()
+    assert lib.count_baseline(None, 4, buf, buf, None) == hm.binding.HM_EINVAL
+    assert lib.count_baseline(None, 4, None, None, None) == hm.binding.HM_EINVAL
+    assert lib.count_exact(None, 4, buf, None) == hm.binding.HM_EINVAL
 
 
 def test_options_host_logic():
