@@ -159,13 +159,22 @@ int count_baseline(const hm_graph* H, int k, int64_t* counts, uint64_t* stats, v
  *                          S_2 = floor(S/6), S_3 = floor(S/2), S_4 = the rest
  *                          (the ratio S_3 = 3 S_2, S_4 = 2 S_2 of the
  *                          appendix's parameter search); k = 3: proportional.
- * A stratum with no hyperedge gets no sample. */
+ * A stratum with no hyperedge gets no sample.  Under HM_ALLOC_PAPER a stratum
+ * with at least one hyperedge gets at least one sample (so S_2 = 1 when
+ * S < 6), which keeps every class's estimate unbiased. */
 #define HM_ALLOC_PROPORTIONAL 0
 #define HM_ALLOC_PAPER 1
 
 /* Sample sizes S_2, S_3, S_4 (host array of 3) for the given fraction in
  * (0, 1] and allocation; S_4 = 0 when k = 3. */
 int hm_sample_sizes(const hm_graph* H, int k, double fraction, int allocation, uint64_t* s_out);
+
+/* The same rule from the stratum sizes alone: n_by_size is a host array of
+ * 3 values |E_2|, |E_3|, |E_4| (the last is ignored when k = 3).  Host
+ * only: needs no device and no graph.
+ * Errors: HM_EINVAL for a NULL argument, a fraction outside (0, 1] or an
+ * unknown allocation; HM_EUNSUPPORTED for k other than 3 or 4. */
+int hm_sample_sizes_for(int k, const uint64_t* n_by_size, double fraction, int allocation, uint64_t* s_out);
 
 /* Write the drawn stratum indices (device uint32 arrays of S_2, S_3, S_4
  * values; pointers for empty strata may be NULL).  Draw i of stratum j is

@@ -29,6 +29,9 @@ def lib():
         i64 = ctypes.c_int64
         _lib.oracle_count_exact.argtypes = [ctypes.c_int, ctypes.c_uint32, u32p, i64, u32p, i64, u32p, i64, i64p]
         _lib.oracle_count_exact.restype = ctypes.c_int
+        _lib.oracle_count_exact_threads.argtypes = [ctypes.c_int, ctypes.c_uint32, u32p, i64, u32p, i64, u32p, i64,
+                                                    ctypes.c_int, i64p]
+        _lib.oracle_count_exact_threads.restype = ctypes.c_int
         _lib.oracle_count_baseline.argtypes = [ctypes.c_int, ctypes.c_uint32, u32p, i64p, i64, u32p, i64, u32p, i64,
                                                u32p, i64, i64p, i64p]
         _lib.oracle_count_baseline.restype = ctypes.c_int
@@ -106,6 +109,18 @@ def count_exact(h, k: int) -> np.ndarray:
     return out
 
 
+def count_exact_threads(h, k: int, n_threads: int = 0):
+    """count_exact with each step of Algorithm 2 / 3 spread over host threads
+    (0: every core).  Returns (counts, threads used)."""
+    nh = h if isinstance(h, Normalised) else normalise(h)
+    out = np.zeros(table(k).n_classes, dtype=np.int64)
+    used = lib().oracle_count_exact_threads(k, nh.n_nodes, _flat(nh, 2), nh.count(2), _flat(nh, 3), nh.count(3),
+                                            _flat(nh, 4), nh.count(4), int(n_threads), out)
+    if used < 0:
+        raise RuntimeError("oracle_count_exact_threads failed")
+    return out, used
+
+
 def count_baseline(h, k: int):
     """Exact counts by the baseline of Section 4.1 (Algorithm 1): ESU on the
     clique projection of every hyperedge, keeping the candidates whose induced
@@ -173,14 +188,17 @@ def sample_sizes(n_by_size: dict, k: int, fraction: float, allocation: int = ALL
 
     Proportional: S_j = ceil(fraction * |E_j|).  Paper split for k = 4
     (appendix: S_3 = 3 S_2, S_4 = 2 S_2): S = ceil(fraction * sum_j |E_j|),
-    S_2 = floor(S / 6), S_3 = floor(S / 2), S_4 = S - S_2 - S_3.  An empty
-    stratum gets no draw.
+    S_2 = floor(S / 6), S_3 = floor(S / 2), S_4 = S - S_2 - S_3, and a stratum
+    with hyperedges gets at least one draw under this split (otherwise the
+    classes of a stratum left undrawn would be estimated as 0, which the
+    unbiasedness of Section 5 rules out).  An empty stratum gets no draw.
     """
     import math
     if allocation == ALLOC_PAPER and k == 4:
         s = math.ceil(fraction * float(sum(n_by_size.get(j, 0) for j in (2, 3, 4))))
         S = {2: s // 6, 3: s // 2}
         S[4] = s - S[2] - S[3]
+        S = {j: max(S[j], 1) for j in S}
     else:
         S = {j: math.ceil(fraction * float(n_by_size.get(j, 0))) for j in range(2, k + 1)}
     return {j: (S.get(j, 0) if n_by_size.get(j, 0) > 0 else 0) for j in range(2, k + 1)}

@@ -66,6 +66,7 @@ SIGNATURES = {
     "count_exact": (_int, [_vp, _int, _vp, _vp]),
     "count_baseline": (_int, [_vp, _int, _vp, _vp, _vp]),
     "hm_sample_sizes": (_int, [_vp, _int, _dbl, _int, _vp]),
+    "hm_sample_sizes_for": (_int, [_int, _vp, _dbl, _int, _vp]),
     "hm_sample_draw": (_int, [_vp, _int, _dbl, _u64, _int, _vp, _vp, _vp, _vp]),
     "count_sampled": (_int, [_vp, _int, _dbl, _u64, _int, _vp, _vp, _vp]),
     "count_sampled_indices": (_int, [_vp, _int, _vp, _u64, _vp, _u64, _vp, _u64, _vp, _vp, _vp]),
@@ -285,6 +286,14 @@ def _ptr(t):
 def hm_sample_sizes(H: Graph, k: int, fraction: float, allocation: int = HM_ALLOC_PROPORTIONAL):
     out = (ctypes.c_uint64 * 3)()
     _check(lib().hm_sample_sizes(H.handle, k, float(fraction), allocation, out))
+    return {2: int(out[0]), 3: int(out[1]), 4: int(out[2])}
+
+
+def hm_sample_sizes_for(k: int, n_by_size, fraction: float, allocation: int = HM_ALLOC_PROPORTIONAL):
+    """Sample sizes from the stratum sizes (|E_2|, |E_3|, |E_4|) alone (host only)."""
+    n = (ctypes.c_uint64 * 3)(*[int(x) for x in n_by_size])
+    out = (ctypes.c_uint64 * 3)()
+    _check(lib().hm_sample_sizes_for(k, n, float(fraction), allocation, out))
     return {2: int(out[0]), 3: int(out[1]), 4: int(out[2])}
 
 

@@ -565,11 +565,14 @@ unsigned mlp_grid(uint64_t n) {
   return unsigned(g);
 }
 
+// Temporaries of one call, released in stream order: the caching allocator
+// hands a block out again only after the work enqueued on st before the
+// release has completed, also when the call returns early on an error.
 struct Bufs {
   std::vector<void*> ptrs;
-  ~Bufs() {
-    for (void* p : ptrs) dfree(p);
-  }
+  hipStream_t st;
+  explicit Bufs(hipStream_t s) : st(s) {}
+  ~Bufs() { dfree_on(ptrs.data(), ptrs.size(), st); }
   template <typename T>
   int get(T** p, uint64_t n) {
     void* q = nullptr;
@@ -621,7 +624,7 @@ int contributions(const hm_graph* H, int k, double* y, hipStream_t st) {
   CountmaxArg cm;
   for (int c = 0; c < 256; ++c) cm.cm[c] = c < t.n_classes[k] ? t.countmax[k][c] : 1;
   constexpr uint64_t kChunk = 16384;
-  Bufs tmp;
+  Bufs tmp(st);
   unsigned long long* ps = nullptr;
   uint32_t* idx = nullptr;
   HM_TRY(tmp.get(&ps, kChunk * 256));
@@ -652,7 +655,7 @@ int contributions(const hm_graph* H, int k, double* y, hipStream_t st) {
 int hh_from_draws(const hm_graph* H, int k, const uint32_t* const idx[5], const uint64_t S[5], const double* w,
                   float* est, int64_t* raw, hipStream_t st) {
   note_use(H, st);
-  Bufs tmp;
+  Bufs tmp(st);
   uint64_t total = 0, row0[5] = {0, 0, 0, 0, 0};
   for (int j = 2; j <= k; ++j) {
     row0[j] = total;
@@ -744,7 +747,7 @@ int build_proposal(const hm_graph* Hc, const hm_model* M, int k, hipStream_t st)
   C->k = k;
   const int ns = strata_bounds(H, k, C->bounds);
   const uint64_t n = C->bounds[ns];
-  Bufs tmp;
+  Bufs tmp(st);
   float *X = nullptr, *out = nullptr, *tstd = nullptr;
   double* q = nullptr;
   uint64_t* db = nullptr;
@@ -798,7 +801,7 @@ int hm_features(const hm_graph* H, int k, float* x, void* stream) {
     hm::set_error("order %d is not supported (3 or 4)", k);
     return HM_EUNSUPPORTED;
   }
-  hm::Bufs tmp;
+  hm::Bufs tmp(static_cast<hipStream_t>(stream));
   return hm::features(H, k, x, tmp, static_cast<hipStream_t>(stream));
 }
 
@@ -834,7 +837,7 @@ int hm_mlp_grad(const float* params, const float* x, const float* t, uint64_t n,
   hipStream_t st = static_cast<hipStream_t>(stream);
   const uint32_t blocks = uint32_t(std::min<uint64_t>((n + 63) / 64 + 1, 256));
   const uint32_t waves = blocks * hm::kWavesPerBlock;
-  hm::Bufs tmp;
+  hm::Bufs tmp(st);
   float* partial = nullptr;
   HM_TRY(tmp.get(&partial, uint64_t(waves) * (hm::kNParams + 1)));
   hm::k_mlp_train<<<blocks, hm::kThreads, 0, st>>>(params, x, t, n, n ? 1.f / float(n) : 0.f, partial);
@@ -889,7 +892,7 @@ int hm_model_train(const hm_graph* H, int k, const hm_train_opts* opts, hm_model
   uint64_t b[5];
   const int ns = hm::strata_bounds(H, k, b);
   const uint64_t n = b[ns];
-  hm::Bufs tmp;
+  hm::Bufs tmp(st);
   float *X = nullptr, *t = nullptr, *Xp = nullptr, *tp = nullptr, *stats = nullptr, *partial = nullptr, *grad = nullptr,
         *m = nullptr, *v = nullptr;
   double* y = nullptr;
@@ -1024,7 +1027,7 @@ int count_sampled_learned(const hm_graph* H, const hm_model* M, int k, double fr
   HM_TRY(hm::sample_sizes(H, k, fraction, HM_ALLOC_PROPORTIONAL, S));
   HM_TRY(hm::build_proposal(H, M, k, st));
   const hm::ProposalCache* C = H->proposal;
-  hm::Bufs tmp;
+  hm::Bufs tmp(st);
   uint64_t total = 0;
   for (int j = 2; j <= k; ++j) total += S[j];
   uint32_t* idx = nullptr;
@@ -1062,7 +1065,7 @@ int count_sampled_weighted_indices(const hm_graph* H, int k, const uint32_t* idx
   const uint32_t* ix[5] = {nullptr, nullptr, idx2, idx3, k == 4 ? idx4 : nullptr};
   const double* pp[5] = {nullptr, nullptr, p2, p3, k == 4 ? p4 : nullptr};
   uint64_t S[5] = {0, 0, s2, s3, k == 4 ? s4 : 0};
-  hm::Bufs tmp;
+  hm::Bufs tmp(st);
   uint64_t total = S[2] + S[3] + S[4];
   double* w = nullptr;
   HM_TRY(tmp.get(&w, total + 1));

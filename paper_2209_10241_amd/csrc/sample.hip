@@ -1184,9 +1184,9 @@ int launch_sampled(const hm_graph* H, int k, const uint32_t* const idx[5], const
     sc.maxcard[c] = c < t.n_classes[k] ? t.maxcard[k][c] : 0;
     sc.countmax[c] = c < t.n_classes[k] ? t.countmax[k][c] : 1;
   }
-  // work queue of heavy samples (order 4 without bit rows); its buffers stay
-  // with the caching allocator, which hands them out again only to work
-  // enqueued after this call
+  // work queue of heavy samples (order 4 without bit rows); its buffers are
+  // released in stream order: the caching allocator hands them out again only
+  // once an event recorded on st after the drain and the finish has completed
   a.q.job = nullptr;
   a.q.cap = 0;
   a.q.tail = H->sample_hist + uint64_t(kHistCopies) * kSampleHistStride + 1;
@@ -1200,11 +1200,9 @@ int launch_sampled(const hm_graph* H, int k, const uint32_t* const idx[5], const
   a.q.inline_work = kInlineWork / scale;
   struct Release {
     void* p[2] = {nullptr, nullptr};
-    ~Release() {
-      dfree(p[0]);
-      dfree(p[1]);
-    }
-  } rel;
+    hipStream_t st;
+    ~Release() { dfree_on(p, 2, st); }
+  } rel{{nullptr, nullptr}, st};
   if (k == 4 && !bits) {
     a.q.cap = std::min<uint64_t>(kQueuePerSample * scale * (a.d.S[2] + a.d.S[3]) + 65536, kQueueMax);
     HM_TRY(dalloc(&rel.p[0], a.q.cap * sizeof(uint4)));
@@ -1231,7 +1229,8 @@ int launch_sampled(const hm_graph* H, int k, const uint32_t* const idx[5], const
 
 }  // namespace
 
-int sample_sizes(const hm_graph* H, int k, double fraction, int allocation, uint64_t* S) {
+// Sample sizes from the stratum sizes n[j] = |E_j| (j = 2..4).
+int sample_sizes_for(const uint64_t n[5], int k, double fraction, int allocation, uint64_t* S) {
   if (k != 3 && k != 4) {
     set_error("order %d is not supported (3 or 4)", k);
     return HM_EUNSUPPORTED;
@@ -1246,18 +1245,24 @@ int sample_sizes(const hm_graph* H, int k, double fraction, int allocation, uint
   }
   for (int j = 0; j < 5; ++j) S[j] = 0;
   if (allocation == HM_ALLOC_PAPER && k == 4) {
-    // S = ceil(f * |E_2 u E_3 u E_4|) split S_2 : S_3 : S_4 = 1 : 3 : 2
-    const double tot = double(H->n_by_size[2] + H->n_by_size[3] + H->n_by_size[4]);
+    // S = ceil(f * |E_2 u E_3 u E_4|) split S_2 : S_3 : S_4 = 1 : 3 : 2; a
+    // stratum with hyperedges gets at least one draw, so that every class
+    // keeps an unbiased estimate however small S is
+    const double tot = double(n[2] + n[3] + n[4]);
     const uint64_t s = uint64_t(std::ceil(fraction * tot));
     S[2] = s / 6;
     S[3] = s / 2;
     S[4] = s - S[2] - S[3];
-    for (int j = 2; j <= 4; ++j)
-      if (H->n_by_size[j] == 0) S[j] = 0;
+    for (int j = 2; j <= 4; ++j) S[j] = n[j] == 0 ? 0 : std::max<uint64_t>(S[j], 1);
   } else {
-    for (int j = 2; j <= k; ++j) S[j] = uint64_t(std::ceil(fraction * double(H->n_by_size[j])));
+    for (int j = 2; j <= k; ++j) S[j] = uint64_t(std::ceil(fraction * double(n[j])));
   }
   return HM_OK;
+}
+
+int sample_sizes(const hm_graph* H, int k, double fraction, int allocation, uint64_t* S) {
+  const uint64_t n[5] = {0, 0, H->n_by_size[2], H->n_by_size[3], H->n_by_size[4]};
+  return sample_sizes_for(n, k, fraction, allocation, S);
 }
 
 // Enumerate around explicit samples (device index arrays): sample s of stratum
@@ -1289,6 +1294,20 @@ int hm_sample_sizes(const hm_graph* H, int k, double fraction, int allocation, u
   }
   uint64_t S[5];
   HM_TRY(hm::sample_sizes(H, k, fraction, allocation, S));
+  s_out[0] = S[2];
+  s_out[1] = S[3];
+  s_out[2] = S[4];
+  return HM_OK;
+}
+
+int hm_sample_sizes_for(int k, const uint64_t* n_by_size, double fraction, int allocation, uint64_t* s_out) {
+  if (!n_by_size || !s_out) {
+    hm::set_error("NULL argument");
+    return HM_EINVAL;
+  }
+  const uint64_t n[5] = {0, 0, n_by_size[0], n_by_size[1], k == 4 ? n_by_size[2] : 0};
+  uint64_t S[5];
+  HM_TRY(hm::sample_sizes_for(n, k, fraction, allocation, S));
   s_out[0] = S[2];
   s_out[1] = S[3];
   s_out[2] = S[4];

@@ -455,11 +455,13 @@ __global__ void k_pl_codeg(View v, const unsigned long long* __restrict__ keys, 
   }
 }
 
+// Temporaries of one call, released in stream order (see dfree_on), also
+// when the call returns early on an error.
 struct Scratch {
   std::vector<void*> ptrs;
-  ~Scratch() {
-    for (void* p : ptrs) dfree(p);
-  }
+  hipStream_t st;
+  explicit Scratch(hipStream_t s) : st(s) {}
+  ~Scratch() { dfree_on(ptrs.data(), ptrs.size(), st); }
   template <typename T>
   int get(T** p, uint64_t n) {
     void* q = nullptr;
@@ -531,7 +533,7 @@ int ensure_node_stats(hm_graph* H, hipStream_t st) {
   if (H->ns_tri) return HM_OK;
   const View v = view_of(H);
   const uint64_t n2 = H->n_by_size[2], n3 = H->n_by_size[3], N = H->n_nodes;
-  Scratch tmp;
+  Scratch tmp(st);
   unsigned long long *acc = nullptr, *tv = nullptr;
   uint32_t* tri_e = nullptr;
   HM_TRY(tmp.get(&acc, kAccN));
@@ -580,7 +582,7 @@ int ensure_edge_stats(hm_graph* H, hipStream_t st) {
   auto* es = static_cast<unsigned long long*>(p_es);
   int rc = fill_u64(es, 0, 6 * n2, st);
   {
-    Scratch tmp;
+    Scratch tmp(st);
     unsigned long long *acc = nullptr, *tv = nullptr;
     uint32_t *tri_e = nullptr, *cnt = nullptr, *touched = nullptr, *outdeg = nullptr, *dmax = nullptr,
              *wlist = nullptr;
@@ -821,7 +823,7 @@ int count_sparse(const hm_graph* H, int k, hipStream_t st) {
   HM_TRY(device_luts(H->device, &lut4, &lut3));
   const View v = view_of(H);
   const uint64_t n2 = H->n_by_size[2], n3 = H->n_by_size[3];
-  Scratch tmp;
+  Scratch tmp(st);
   unsigned long long *acc = nullptr, *tv = nullptr;
   uint32_t* tri_e = nullptr;
   HM_TRY(tmp.get(&acc, kAccN));

@@ -93,3 +93,29 @@ def test_bench_refuses_several_gpus():
     r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True, text=True,
                        timeout=120)
     assert r.returncode == 2 and "one GPU" in r.stderr
+
+
+def test_sample_sizes_rule():
+    """Stratum sample sizes (Section 5; the 1:3:2 split of the appendix's
+    parameter search), host only: proportional is ceil(f |E_j|); the paper's
+    split gives every non-empty stratum at least one draw and an empty one none."""
+    import math
+    import paper_2209_10241_amd as hm
+    n = (1000, 400, 37)
+    got = hm.hm_sample_sizes_for(4, n, 0.013)
+    assert got == {2: math.ceil(0.013 * 1000), 3: math.ceil(0.013 * 400), 4: math.ceil(0.013 * 37)}
+    assert hm.hm_sample_sizes_for(3, n, 0.5) == {2: 500, 3: 200, 4: 0}
+    # S = ceil(0.1 * 1437) = 144 -> 24 / 72 / 48
+    assert hm.hm_sample_sizes_for(4, n, 0.1, hm.HM_ALLOC_PAPER) == {2: 24, 3: 72, 4: 48}
+    # S = ceil(0.001 * 1437) = 2 < 6: floor(S/6) would leave the pairs undrawn
+    small = hm.hm_sample_sizes_for(4, n, 0.001, hm.HM_ALLOC_PAPER)
+    assert small == {2: 1, 3: 1, 4: 1}
+    assert hm.hm_sample_sizes_for(4, (0, 400, 37), 0.001, hm.HM_ALLOC_PAPER)[2] == 0
+    for bad in (0.0, 1.5, float("nan")):
+        with pytest.raises(hm.HMError):
+            hm.hm_sample_sizes_for(4, n, bad)
+    with pytest.raises(hm.HMError):
+        hm.hm_sample_sizes_for(4, n, 0.1, 7)
+    with pytest.raises(hm.HMError) as e:
+        hm.hm_sample_sizes_for(5, n, 0.1)
+    assert e.value.code == -2

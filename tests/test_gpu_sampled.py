@@ -259,3 +259,31 @@ def test_hub_rows_census(hm, hub_rows):
         est, raw = hm.count_sampled_indices(g, 4, samples)
         countmax = np.array([hm.hm_class_info(4, c)[2] for c in range(len(exact))])
     assert np.array_equal(raw.cpu().numpy(), exact * countmax)
+
+
+def test_queue_buffers_outlive_the_call(hm, queued):
+    """count_sampled returns before its kernels finish; the work queue it
+    allocated is released in stream order, so a graph built and counted on
+    another stream right after cannot be handed those blocks while the
+    drain still reads them: the first call's raw counts stay exact."""
+    import torch
+    h = W.scaled_communication(0.004, 0)
+    nh = core.normalise(h)
+    want_raw, want_est, _, _ = _oracle_sampled(nh, 4, 0.2, 31)
+    hb = W.random_small(4600, 60, 900, {2: 0.5, 3: 0.3, 4: 0.2})
+    want_b = core.count_exact(hb, 4)
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    with _graph(hm, h, False) as ga:
+        with torch.cuda.stream(s1):
+            hm.count_sampled(ga, 4, 0.2, 31, 0)      # builds the graph's cached indices
+            s1.synchronize()
+            est, raw = hm.count_sampled(ga, 4, 0.2, 31, 0)
+        with torch.cuda.stream(s2):
+            for _ in range(3):
+                with _graph(hm, hb, False) as gb:
+                    hm.count_sampled(gb, 4, 0.5, 7, 0)
+                    got_b = hm.count_exact(gb, 4)
+        torch.cuda.synchronize()
+    assert np.array_equal(raw.cpu().numpy(), want_raw)
+    assert np.array_equal(est.cpu().numpy(), want_est)
+    assert np.array_equal(got_b.cpu().numpy(), want_b)
