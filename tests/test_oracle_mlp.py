@@ -1,6 +1,8 @@
 """Pins of the learned proposal's reference: finite differences for the
-gradient, the bfloat16 rounding rule, and the Hansen-Hurwitz estimator
-reducing to the correction of Algorithm 4 under uniform probabilities."""
+gradient, the bfloat16 rounding rule, the rounding-error bound (it covers a
+computation rounded at the kernels' points and catches planted mistakes),
+and the Hansen-Hurwitz estimator reducing to the correction of Algorithm 4
+under uniform probabilities."""
 import numpy as np
 import pytest
 
@@ -43,14 +45,79 @@ def test_bf16_rounding_rule():
     assert np.all((r.view(np.uint32) & 0xFFFF) == 0)
 
 
-def test_mirrored_gradient_is_close_to_exact():
-    rng = np.random.default_rng(7)
+def _bf16(a):
+    return mlp.bf16(np.asarray(a, dtype=np.float32))
+
+
+def _rounded_network(p, x, t, plant=None):
+    """A computation with the kernels' precision, in this test only: operands of
+    the hidden-layer products rounded to bfloat16 (nearest even), everything
+    else float32.  ``plant`` puts a plausible mistake into it."""
+    W1, b1, W2, b2, w3, b3 = [np.asarray(a, dtype=np.float32) for a in mlp.unpack(p)]
+    x = np.asarray(x, np.float32)
+    t = np.asarray(t, np.float32)
+    B = len(x)
+    if plant == "transposed_W2":
+        W2 = np.ascontiguousarray(W2.T)
+    xb = _bf16(x)
+    z1 = xb @ _bf16(W1).T + b1
+    h1b = _bf16(np.maximum(z1, 0))
+    z2 = h1b @ _bf16(W2).T + (0 if plant == "dropped_b2" else b2)
+    h2 = np.maximum(z2, 0)
+    out = h2 @ w3 + b3
+    dout = np.float32(2) * (out - t) * np.float32(1 / B)
+    if plant == "sign":
+        dout = -dout
+    g = np.zeros(mlp.N_PARAMS, np.float32)
+    g[mlp.OFF_W3:mlp.OFF_B3] = dout @ h2
+    g[mlp.OFF_B3] = dout.sum()
+    dz2 = np.outer(dout, w3) * (z2 > 0)
+    g[mlp.OFF_B2:mlp.OFF_W3] = dz2.sum(0)
+    dz2b = _bf16(dz2)
+    g[mlp.OFF_W2:mlp.OFF_B2] = (dz2b.T @ h1b).reshape(-1)
+    dh1 = dz2b @ _bf16(W2)
+    dz1 = dh1 * (z1 > 0) if plant != "no_relu_mask" else dh1
+    g[mlp.OFF_B1:mlp.OFF_W2] = dz1.sum(0)
+    g[mlp.OFF_W1:mlp.OFF_B1] = (_bf16(dz1).T @ xb).reshape(-1)
+    return out, g, float(np.mean((out.astype(np.float64) - t) ** 2))
+
+
+def _within(r, out, g, loss):
+    return (np.all(np.abs(out - r["out"]) <= r["out_bound"])
+            and np.linalg.norm(out - r["out"]) <= 2 * r["out_dev_norm"]
+            and np.all(np.abs(g - r["grad"]) <= r["grad_bound"])
+            and np.linalg.norm(g - r["grad"]) <= 2 * r["grad_dev_norm"]
+            and abs(loss - r["loss"]) <= r["loss_bound"])
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_bound_covers_a_rounded_computation(seed):
+    """The per-element bound (and twice the largest deviation norm of its
+    runs) covers a computation rounded at the kernels' points."""
+    rng = np.random.default_rng(300 + seed)
+    B = [1, 16, 50, 257][seed % 4]
+    p = rng.normal(0, 0.3, mlp.N_PARAMS)
+    x = rng.normal(size=(B, 16))
+    t = rng.normal(size=B)
+    r = mlp.error_bounds(p, x, t, seed=seed)
+    assert _within(r, *_rounded_network(p, x, t))
+
+
+def test_bound_is_informative():
+    """The bound is small beside the values where rounding is mild, and each
+    planted mistake breaks it."""
+    rng = np.random.default_rng(11)
+    p = rng.normal(0, 0.3, mlp.N_PARAMS)
     x = rng.normal(size=(64, 16))
     t = rng.normal(size=64)
-    p = _params(7)
-    _, g = mlp.loss_and_grad(p, x, t)
-    _, gm = mlp.loss_and_grad(p, x, t, mirror=True)
-    assert np.linalg.norm(gm - g) < 0.05 * np.linalg.norm(g)
+    r = mlp.error_bounds(p, x, t)
+    assert np.median(r["out_bound"] / np.abs(r["out"])) < 0.1
+    g, b = r["grad"], r["grad_bound"]
+    for lo, hi in ((mlp.OFF_W2, mlp.OFF_B2), (mlp.OFF_B2, mlp.OFF_W3), (mlp.OFF_W3, mlp.OFF_B3)):
+        nz = g[lo:hi] != 0
+        assert np.median(b[lo:hi][nz] / np.abs(g[lo:hi][nz])) < 0.3
+    for plant in ("transposed_W2", "dropped_b2", "sign", "no_relu_mask"):
+        assert not _within(r, *_rounded_network(p, x, t, plant)), plant
 
 
 def test_hansen_hurwitz_uniform_is_algorithm4():
