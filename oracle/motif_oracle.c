@@ -18,10 +18,12 @@
  *   - fill-in of a node set and its isomorphism class (Section 4.3)
  *   - ESU (Wernicke 2006), used by Algorithms 2 and 3 on the pairwise graph
  *     and by Algorithm 1 on the clique projection
- *   - Algorithm 2 (order 3) and Algorithm 3 (order 4), exact
+ *   - Algorithm 2 (order 3) and Algorithm 3 (order 4), exact, on one thread
+ *     and spread over host threads
  *   - Algorithm 1 (the baseline of Section 4.1), exact
  *   - Algorithm 4, sampled, on an explicit list of sampled hyperedges
  */
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -433,23 +435,27 @@ static void esu_extend(esu_ctx *c, uint32_t *Vsub, int nsub, const uint32_t *Vex
     free(ext);
 }
 
+/* the sets whose smallest node is v */
+static void esu_root(esu_ctx *c, uint32_t v)
+{
+    int64_t deg = c->off[v + 1] - c->off[v];
+    uint32_t *ext = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)(deg + 1));
+    if (!ext) { c->failed = 1; return; }
+    int64_t n = 0;
+    for (int64_t i = 0; i < deg; i++) {
+        uint32_t u = c->adj[c->off[v] + i];
+        if (u > v) ext[n++] = u;
+    }
+    uint32_t Vsub[4] = { v, 0, 0, 0 };
+    esu_extend(c, Vsub, 1, ext, n, v);
+    free(ext);
+}
+
 static void esu(const int64_t *off, const uint32_t *adj, uint32_t n_nodes, int k,
                 void (*emit)(void *, const uint32_t *), void *ctx, int *failed)
 {
     esu_ctx c = { off, adj, k, emit, ctx, 0 };
-    for (uint32_t v = 0; v < n_nodes && !c.failed; v++) {
-        int64_t deg = off[v + 1] - off[v];
-        uint32_t *ext = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)(deg + 1));
-        if (!ext) { c.failed = 1; break; }
-        int64_t n = 0;
-        for (int64_t i = 0; i < deg; i++) {
-            uint32_t u = adj[off[v] + i];
-            if (u > v) ext[n++] = u;
-        }
-        uint32_t Vsub[4] = { v, 0, 0, 0 };
-        esu_extend(&c, Vsub, 1, ext, n, v);
-        free(ext);
-    }
+    for (uint32_t v = 0; v < n_nodes && !c.failed; v++) esu_root(&c, v);
     *failed = c.failed;
 }
 
@@ -553,6 +559,149 @@ int oracle_count_exact(int k, uint32_t n_nodes,
     if (failed) return -1;
     memcpy(counts, M, sizeof(int64_t) * (size_t)n_class[k]);
     return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* Algorithms 2 and 3 on several host threads (OpenMP).                */
+/* The same three steps in the same order, each spread over threads;   */
+/* `visited` is a set of node sets, so which thread inserts a set      */
+/* first does not change which sets are counted: a set is counted by   */
+/* the one insertion that finds it absent (steps 1 and 2), and step 3  */
+/* only reads the set, which ESU's one-emission-per-set allows.  The   */
+/* counts equal the single-thread routine's (tests check it).          */
+/* ------------------------------------------------------------------ */
+#define N_SHARDS 256
+
+typedef struct {
+    tupset s[N_SHARDS];
+    omp_lock_t lock[N_SHARDS];
+} shardset;
+
+static int shard_of(const tup *t) { return (int)(tup_hash(t) >> 56) & (N_SHARDS - 1); }
+
+/* 1 if added, 0 if present, -1 on allocation failure */
+static int shard_add(shardset *ss, const tup *t)
+{
+    int h = shard_of(t);
+    omp_set_lock(&ss->lock[h]);
+    int r = tupset_add(&ss->s[h], t);
+    omp_unset_lock(&ss->lock[h]);
+    return r;
+}
+
+typedef struct {
+    const hgraph *g;
+    int k;
+    shardset *visited;
+    int64_t *M;
+    int failed;
+} mt_ctx;
+
+static void mt_emit_unvisited(void *p, const uint32_t *V)
+{
+    mt_ctx *c = (mt_ctx *)p;
+    tup t = make_tup(V, c->k);
+    const tupset *s = &c->visited->s[shard_of(&t)];
+    if (tupset_has(s, &t)) return;
+    int cls = pattern_class(fill_in(c->g, V, c->k), c->k);
+    if (cls < 0) { c->failed = 1; return; }
+    c->M[cls]++;
+}
+
+/* oracle_count_exact on up to n_threads threads (0: all the host's).
+ * Returns the number of threads used, or -1 on bad arguments or allocation
+ * failure. */
+int oracle_count_exact_threads(int k, uint32_t n_nodes,
+                               const uint32_t *e2, int64_t n2, const uint32_t *e3, int64_t n3,
+                               const uint32_t *e4, int64_t n4, int n_threads, int64_t *counts)
+{
+    if (k != 3 && k != 4) return -1;
+    build_tables();
+    if (n_threads <= 0) n_threads = omp_get_num_procs();
+    hgraph g;
+    if (hgraph_build(&g, k, n_nodes, e2, n2, e3, n3, e4, n4) != 0) { hgraph_free(&g); return -1; }
+    shardset *vis = (shardset *)calloc(1, sizeof(shardset));
+    int failed = !vis;
+    for (int h = 0; h < N_SHARDS && !failed; h++) {
+        if (tupset_init(&vis->s[h], 64) != 0) failed = 1;
+        omp_init_lock(&vis->lock[h]);
+    }
+    int64_t M[256];
+    memset(M, 0, sizeof(M));
+    int used = 1;
+    if (!failed) {
+        #pragma omp parallel num_threads(n_threads)
+        {
+            int64_t Mt[256];
+            memset(Mt, 0, sizeof(Mt));
+            int bad = 0;
+            #pragma omp single
+            used = omp_get_num_threads();
+            /* step 1: the k-node hyperedges; their node sets are visited */
+            const int64_t n_top = g.ne[k];
+            #pragma omp for schedule(dynamic, 256)
+            for (int64_t i = 0; i < n_top; i++) {
+                const uint32_t *V = g.e[k] + (size_t)k * i;
+                int cls = pattern_class(fill_in(&g, V, k), k);
+                if (cls < 0) { bad = 1; continue; }
+                Mt[cls]++;
+                tup t = make_tup(V, k);
+                if (shard_add(vis, &t) < 0) bad = 1;
+            }
+            /* (implicit barrier) step 2 at order 4: 3-node hyperedges with
+             * every adjacent hyperedge of size 2 or 3 adding one node */
+            if (k == 4) {
+                #pragma omp for schedule(dynamic, 64)
+                for (int64_t i = 0; i < g.ne[3]; i++) {
+                    const uint32_t *e = g.e[3] + 3 * i;
+                    for (int m = 0; m < 3; m++) {
+                        uint32_t u = e[m];
+                        for (int64_t x = g.inc_off[u]; x < g.inc_off[u + 1]; x++) {
+                            int fs = g.inc_size[x];
+                            if (fs > 3) continue;
+                            const uint32_t *f = g.e[fs] + (size_t)g.inc_idx[x] * fs;
+                            uint32_t U[7];
+                            int nu = 0;
+                            for (int a = 0; a < 3; a++) U[nu++] = e[a];
+                            for (int a = 0; a < fs; a++) {
+                                int in = 0;
+                                for (int b = 0; b < 3; b++) if (e[b] == f[a]) in = 1;
+                                if (!in) U[nu++] = f[a];
+                            }
+                            if (nu != 4) continue;
+                            sort_nodes(U, 4);
+                            tup t = make_tup(U, 4);
+                            int r = shard_add(vis, &t);
+                            if (r < 0) { bad = 1; continue; }
+                            if (r == 0) continue;
+                            int cls = pattern_class(fill_in(&g, U, 4), 4);
+                            if (cls < 0) { bad = 1; continue; }
+                            Mt[cls]++;
+                        }
+                    }
+                }
+            }
+            /* last step: ESU on the pairwise graph, roots spread over threads */
+            mt_ctx c = { &g, k, vis, Mt, 0 };
+            esu_ctx ec = { g.g2_off, g.g2_adj, k, mt_emit_unvisited, &c, 0 };
+            #pragma omp for schedule(dynamic, 1)
+            for (int64_t v = 0; v < (int64_t)g.n_nodes; v++) esu_root(&ec, (uint32_t)v);
+            if (c.failed || ec.failed) bad = 1;
+            #pragma omp critical
+            {
+                for (int i = 0; i < 256; i++) M[i] += Mt[i];
+                if (bad) failed = 1;
+            }
+        }
+    }
+    if (vis) {
+        for (int h = 0; h < N_SHARDS; h++) { tupset_free(&vis->s[h]); omp_destroy_lock(&vis->lock[h]); }
+        free(vis);
+    }
+    hgraph_free(&g);
+    if (failed) return -1;
+    memcpy(counts, M, sizeof(int64_t) * (size_t)n_class[k]);
+    return used;
 }
 
 /* ------------------------------------------------------------------ */

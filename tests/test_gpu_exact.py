@@ -91,6 +91,68 @@ def test_communication_scaled_workload(hm, bit_rows):
     assert np.array_equal(_gpu_counts(hm, h, 4, bit_rows), _golden("communication_scaled_0.004", 4))
 
 
+def _heavy_goldens():
+    with open(os.path.join(ROOT, "tests", "golden", "workload_counts.json")) as f:
+        names = [c["workload"] for c in json.load(f)["cases"]]
+    out = []
+    for name in names:
+        for family, maker in (("communication", W.scaled_communication), ("coauthorship", W.scaled_coauthorship)):
+            prefix = f"{family}_scaled_"
+            if name.startswith(prefix) and name != "communication_scaled_0.004":
+                out.append((name, maker, float(name[len(prefix):])))
+    return out
+
+
+@pytest.mark.parametrize("bit_rows", [True, False], ids=["bits", "hash"])
+@pytest.mark.parametrize("name,maker,scale", _heavy_goldens(), ids=[c[0] for c in _heavy_goldens()])
+def test_heavy_tailed_scaled_goldens(hm, name, maker, scale, bit_rows):
+    """The heavy-tailed recipes at the largest fractions of their size whose
+    oracle counts are stored (Algorithm 3 on every host core): both GPU paths
+    bit-exact.  Graphs with more nodes than bit rows hold have one path."""
+    h = maker(scale, 0)
+    if bit_rows and h.n_nodes > 8192:
+        pytest.skip(f"{h.n_nodes} nodes: more than adjacency bit rows hold, the hash path is the only one")
+    assert np.array_equal(_gpu_counts(hm, h, 4, bit_rows), _golden(name, 4))
+
+
+@pytest.fixture(scope="module")
+def full_size():
+    """The co-authorship (10^6 nodes, 2x10^6 draws) and communication (5x10^4
+    nodes, 5x10^6 draws) workloads at full size, generated once."""
+    out = {}
+    for name, maker in (("coauthorship", W.cfg3_coauthorship), ("communication", W.cfg4_communication)):
+        print(f"generating {name}", flush=True)
+        out[name] = maker(0)
+    return out
+
+
+@pytest.mark.parametrize("name", ["coauthorship", "communication"])
+def test_full_size_relabelling_and_census(hm, full_size, name):
+    """At full size, where the oracle cannot run: (1) the exact counts do not
+    change under a fixed node relabelling (Section 3: a motif is an
+    isomorphism class), and (2) a census through the sampler - every
+    hyperedge of size 2..4 drawn exactly once (Algorithm 4 with S_j = |E_j|)
+    - gives raw counts countmax_m * n_m for every class and estimates equal to
+    the exact counts.  The sampler enumerates each hyperedge's neighbourhood;
+    the exact count uses graph identities and ownership rules: two
+    independent routes to the same int64 vector."""
+    h = full_size[name]
+    with hm.hm_graph_create(h.members, h.offsets, h.n_nodes) as g:
+        exact = hm.count_exact(g, 4).cpu().numpy()
+        st = g.stats()
+        samples = {j: np.arange(st[f"n{j}"]) for j in range(2, 5)}
+        print(f"{name}: census of {sum(len(v) for v in samples.values())} hyperedges", flush=True)
+        est, raw = hm.count_sampled_indices(g, 4, samples)
+    countmax = np.array([hm.hm_class_info(4, c)[2] for c in range(len(exact))], dtype=np.int64)
+    assert exact.sum() > 10**12
+    assert np.array_equal(raw.cpu().numpy(), exact * countmax)
+    assert np.array_equal(est.cpu().numpy(), exact.astype(np.float32))
+    perm = np.random.default_rng(11).permutation(h.n_nodes)
+    hp = W.Hypergraph(h.n_nodes, perm[h.members.astype(np.int64)].astype(np.uint32), h.offsets.copy())
+    print(f"{name}: relabelled count", flush=True)
+    assert np.array_equal(_gpu_counts(hm, hp, 4), exact)
+
+
 @pytest.mark.parametrize("scale", [0.02, 0.05])
 def test_sparse_path_agrees_with_bit_rows(hm, scale):
     """Larger heavy-tailed graphs: the counting formulas without bit rows and the

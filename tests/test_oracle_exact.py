@@ -236,3 +236,26 @@ def test_input_errors():
         core.normalise(W.from_lists([[0, 5]], 3))
     with pytest.raises(core.InputError):
         core.normalise(W.Hypergraph(3, np.array([0, 1], np.uint32), np.array([0, 0, 2], np.uint64)))
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_threaded_algorithms_match_brute_force(seed):
+    """Algorithms 2 and 3 spread over host threads give the single-thread
+    counts and brute force's (set semantics of `visited`)."""
+    mix = SIZE_MIXES[seed % len(SIZE_MIXES)]
+    h = W.random_small(500 + seed, 10 + seed % 9, 20 + 5 * (seed % 7), mix, allow_dups=bool(seed % 2))
+    for k in (3, 4):
+        want = brute.count_brute(h, k)
+        for threads in (1, 3, 8):
+            got, used = core.count_exact_threads(h, k, threads)
+            assert used == threads
+            assert np.array_equal(got, want), (seed, k, threads)
+
+
+def test_threaded_matches_single_thread_on_workloads(golden_dir):
+    with open(os.path.join(golden_dir, "workload_counts.json")) as f:
+        cases = {(c["workload"], c["k"]): np.array(c["counts"]) for c in json.load(f)["cases"] if "copy" not in c}
+    h = W.cfg0_facetoface_k3(0)
+    assert np.array_equal(core.count_exact_threads(h, 3)[0], cases[("facetoface_N200_E2000", 3)])
+    h = W.scaled_communication(0.004, 0)
+    assert np.array_equal(core.count_exact_threads(h, 4)[0], cases[("communication_scaled_0.004", 4)])
