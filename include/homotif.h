@@ -131,6 +131,25 @@ int hm_graph_export(const hm_graph* H, int j, uint32_t* out);
  * overwritten.  Asynchronous on `stream`. */
 int count_exact(const hm_graph* H, int k, int64_t* counts, void* stream);
 
+/* count_exact for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * Same arguments, same counts, and no hipMalloc, hipFree or other device
+ * allocation in the call: its per-class counters (16 copies of 3 x 256
+ * int64) and the class tables live in a fixed device array of the library
+ * (about 130 KB, one per device, held until the process ends), whose device
+ * address is looked up on the first call on each device.
+ * Limit: graphs with adjacency bit rows only (at most
+ * HM_OPT_BITSET_MAX_NODES nodes, 8192 by default): counting without them
+ * needs temporaries sized by the graph.
+ * Every call on one device shares that array, which keeps the last call's
+ * contents; each call clears what it needs first.  Calls that overlap on one
+ * device (on different streams, or from several threads) race and give
+ * wrong counts: the caller serialises them.
+ * Errors: HM_EINVAL for a NULL argument or when the current device is not
+ * the graph's; HM_EUNSUPPORTED for k other than 3 or 4 or a graph without
+ * bit rows; HM_EDEVICE when the array's address cannot be obtained. */
+int count_exact_noalloc(const hm_graph* H, int k, int64_t* counts, void* stream);
+
 /* Exact counts of every order-k motif (k = 3 or 4) by the baseline of
  * Section 4.1 (Algorithm 1): the clique projection G of the hypergraph (two
  * nodes joined when a hyperedge of any size >= 2 holds both), every connected

@@ -7,6 +7,6 @@ from .binding import (  # noqa: F401
     Model, count_sampled_learned, count_sampled_weighted_indices, hm_contrib, hm_features, hm_mlp_forward,
     hm_mlp_grad, hm_model_train, hm_proposal_probs,
     hm_get_option, hm_sample_draw, hm_sample_sizes, hm_sample_sizes_for, hm_set_option,
-    Graph, HMError, LibraryMissing, count_baseline, count_exact, hm_class_info, hm_graph_create, hm_num_classes,
+    Graph, HMError, LibraryMissing, count_baseline, count_exact, count_exact_noalloc, hm_class_info, hm_graph_create, hm_num_classes,
     hm_pattern_class, hm_profile_enable, hm_profile_read, hm_profile_reset, hm_version, lib,
 )

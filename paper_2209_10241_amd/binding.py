@@ -64,6 +64,7 @@ SIGNATURES = {
     "hm_graph_stats": (_int, [_vp, _vp]),
     "hm_graph_export": (_int, [_vp, _int, _vp]),
     "count_exact": (_int, [_vp, _int, _vp, _vp]),
+    "count_exact_noalloc": (_int, [_vp, _int, _vp, _vp]),
     "count_baseline": (_int, [_vp, _int, _vp, _vp, _vp]),
     "hm_sample_sizes": (_int, [_vp, _int, _dbl, _int, _vp]),
     "hm_sample_sizes_for": (_int, [_int, _vp, _dbl, _int, _vp]),
@@ -229,6 +230,15 @@ def count_exact(H: Graph, k: int, out=None, stream=None):
     if out is None:
         out = torch.empty(n, dtype=torch.int64, device="cuda")
     _check(lib().count_exact(H.handle, k, ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)))
+    return out
+
+
+def count_exact_noalloc(H: Graph, k: int, out=None, stream=None):
+    """count_exact without device allocation in the library (graphs with bit rows)."""
+    import torch
+    if out is None:
+        out = torch.empty(hm_num_classes(k), dtype=torch.int64, device="cuda")
+    _check(lib().count_exact_noalloc(H.handle, k, ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)))
     return out
 
 

@@ -10,6 +10,7 @@
 // held in LDS; per-class counters live in LDS and are flushed to device
 // memory with one atomic per class per workgroup.
 #include <algorithm>
+#include <cstring>
 #include <map>
 #include <mutex>
 #include <tuple>
@@ -252,6 +253,91 @@ unsigned grid_threads(uint64_t items, unsigned cap = kCountGrid, unsigned per_bl
   return unsigned(g);
 }
 
+// The fused counting launch of a graph with adjacency bit rows, adding to the
+// kHistCopies counter copies at hist (main, sub and G2 regions).
+void launch_bits_count(const hm_graph* H, int k, const uint8_t* lut, unsigned long long* hist, hipStream_t st) {
+  const View v = view_of(H);
+  const uint64_t n2 = H->n_by_size[2], n3 = H->n_by_size[3], n4 = H->n_by_size[4];
+  ExactArgs a{};
+  a.v = v;
+  a.n2 = n2;
+  a.n3 = n3;
+  a.n4 = k == 4 ? n4 : 0;
+  a.lut = lut;
+  a.hist = hist;
+  if (k == 4) {
+    const size_t rows = (size_t(v.N) * v.W + 3 * (size_t(v.N) + 1)) * 4;
+    const bool lb = rows <= kLdsBitsMaxBytes;
+    const size_t lds = size_t(kExact4Waves) * b4_set_words(v.W) * 4 + (lb ? rows : 0);
+    const uint64_t items = n2 + n3 + (n4 + kA4Chunk - 1) / kA4Chunk;
+    const void* kern = lb ? reinterpret_cast<const void*>(k_exact4_bits<true>)
+                          : reinterpret_cast<const void*>(k_exact4_bits<false>);
+    const unsigned grid = fused_grid(kern, lds, items, kExact4Waves, kExact4Threads);
+    ProfileScope ps("k_exact4_bits", st);
+    if (lb)
+      k_exact4_bits<true><<<grid, kExact4Threads, lds, st>>>(a);
+    else
+      k_exact4_bits<false><<<grid, kExact4Threads, lds, st>>>(a);
+  } else {
+    const unsigned grid = fused_grid(reinterpret_cast<const void*>(k_exact3_bits), 0, n2 * v.W + n3, kThreads);
+    ProfileScope ps("k_exact3_bits", st);
+    k_exact3_bits<<<grid, kThreads, 0, st>>>(a);
+  }
+}
+
+ClassMask pairs_only_mask(int k) {
+  const ClassTables& t = class_tables();
+  ClassMask m{{0, 0, 0, 0}};
+  for (int c = 0; c < t.n_classes[k]; ++c)
+    if (t.maxcard[k][c] == 2) m.w[c >> 6] |= 1ull << (c & 63);
+  return m;
+}
+
+// ------------------------------------------------------- allocation-free count
+// count_exact_noalloc keeps its counters and class tables in this file-scope
+// device array: kHistCopies x kExactHistStride counters, then the order-4 and
+// order-3 pattern->class tables.  Each device holds its own copy for the
+// life of the process; host code reaches it only through the address
+// hipGetSymbolAddress gives on that device.
+constexpr size_t kNoAllocHistWords = size_t(kHistCopies) * kExactHistStride;
+constexpr size_t kNoAllocLutBytes = 2048 + 16;
+constexpr size_t kNoAllocWords = kNoAllocHistWords + (kNoAllocLutBytes + 7) / 8;
+__device__ __align__(256) unsigned long long scratch[kNoAllocWords];
+
+struct LutArg {
+  uint8_t b[kNoAllocLutBytes];
+};
+
+// Clear the counter copies and write both class tables (passed by value, so
+// that no host copy or device buffer is needed).
+__global__ void k_noalloc_prepare(unsigned long long* __restrict__ s, LutArg luts) {
+  const uint64_t i0 = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  for (uint64_t i = i0; i < kNoAllocHistWords; i += uint64_t(gridDim.x) * blockDim.x) s[i] = 0;
+  uint8_t* lut = reinterpret_cast<uint8_t*>(s + kNoAllocHistWords);
+  for (uint64_t i = i0; i < kNoAllocLutBytes; i += uint64_t(gridDim.x) * blockDim.x) lut[i] = luts.b[i];
+}
+
+std::mutex g_noalloc_mu;
+std::vector<unsigned long long*> g_noalloc_ptr;   // per device
+
+// The device address of `scratch` on device dev, looked up once per device.
+int noalloc_scratch(int dev, unsigned long long** out) {
+  std::lock_guard<std::mutex> lock(g_noalloc_mu);
+  if (size_t(dev) >= g_noalloc_ptr.size()) g_noalloc_ptr.resize(size_t(dev) + 1, nullptr);
+  if (!g_noalloc_ptr[size_t(dev)]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      (void)hipGetLastError();
+      set_error("hipGetSymbolAddress of the counting scratch failed on device %d: %s", dev, hipGetErrorString(e));
+      return HM_EDEVICE;
+    }
+    g_noalloc_ptr[size_t(dev)] = static_cast<unsigned long long*>(p);
+  }
+  *out = g_noalloc_ptr[size_t(dev)];
+  return HM_OK;
+}
+
 }  // namespace
 
 int count_exact_impl(const hm_graph* H, int k, int64_t* counts, hipStream_t st) {
@@ -259,9 +345,7 @@ int count_exact_impl(const hm_graph* H, int k, int64_t* counts, hipStream_t st) 
   const uint8_t *lut4 = nullptr, *lut3 = nullptr;
   HM_TRY(device_luts(H->device, &lut4, &lut3));
   const ClassTables& t = class_tables();
-  ClassMask pairs_only{{0, 0, 0, 0}};
-  for (int c = 0; c < t.n_classes[k]; ++c)
-    if (t.maxcard[k][c] == 2) pairs_only.w[c >> 6] |= 1ull << (c & 63);
+  const ClassMask pairs_only = pairs_only_mask(k);
   // H->hist is zero between calls; a call that fails part-way clears it on
   // the next call
   if (H->hist_dirty) {
@@ -275,34 +359,10 @@ int count_exact_impl(const hm_graph* H, int k, int64_t* counts, hipStream_t st) 
       if (!ok) H->hist_dirty = true;
     }
   } guard{H};
-  const uint64_t n2 = H->n_by_size[2], n3 = H->n_by_size[3], n4 = H->n_by_size[4];
+  const uint64_t n3 = H->n_by_size[3], n4 = H->n_by_size[4];
   const View v = view_of(H);
   if (v.bits) {
-    ExactArgs a{};
-    a.v = v;
-    a.n2 = n2;
-    a.n3 = n3;
-    a.n4 = k == 4 ? n4 : 0;
-    a.lut = k == 4 ? lut4 : lut3;
-    a.hist = H->hist;
-    if (k == 4) {
-      const size_t rows = (size_t(v.N) * v.W + 3 * (size_t(v.N) + 1)) * 4;
-      const bool lb = rows <= kLdsBitsMaxBytes;
-      const size_t lds = size_t(kExact4Waves) * b4_set_words(v.W) * 4 + (lb ? rows : 0);
-      const uint64_t items = n2 + n3 + (n4 + kA4Chunk - 1) / kA4Chunk;
-      const void* kern = lb ? reinterpret_cast<const void*>(k_exact4_bits<true>)
-                            : reinterpret_cast<const void*>(k_exact4_bits<false>);
-      const unsigned grid = fused_grid(kern, lds, items, kExact4Waves, kExact4Threads);
-      ProfileScope ps("k_exact4_bits", st);
-      if (lb)
-        k_exact4_bits<true><<<grid, kExact4Threads, lds, st>>>(a);
-      else
-        k_exact4_bits<false><<<grid, kExact4Threads, lds, st>>>(a);
-    } else {
-      const unsigned grid = fused_grid(reinterpret_cast<const void*>(k_exact3_bits), 0, n2 * v.W + n3, kThreads);
-      ProfileScope ps("k_exact3_bits", st);
-      k_exact3_bits<<<grid, kThreads, 0, st>>>(a);
-    }
+    launch_bits_count(H, k, k == 4 ? lut4 : lut3, H->hist, st);
   } else {
     if (k == 4 && n4) {
       ProfileScope ps("k_case_a4", st);
@@ -334,4 +394,43 @@ extern "C" int count_exact(const hm_graph* H, int k, int64_t* counts, void* stre
     return HM_EUNSUPPORTED;
   }
   return hm::count_exact_impl(H, k, counts, static_cast<hipStream_t>(stream));
+}
+
+extern "C" int count_exact_noalloc(const hm_graph* H, int k, int64_t* counts, void* stream) {
+  if (!H || !counts) {
+    hm::set_error("NULL argument to count_exact_noalloc");
+    return HM_EINVAL;
+  }
+  if (k != 3 && k != 4) {
+    hm::set_error("order %d is not supported (3 or 4)", k);
+    return HM_EUNSUPPORTED;
+  }
+  if (!H->bits) {
+    hm::set_error("count_exact_noalloc counts graphs with adjacency bit rows only (at most %u nodes); this one has "
+                  "%u, and counting it without bit rows needs temporaries sized by the graph",
+                  hm::bitset_max_nodes(), H->n_nodes);
+    return HM_EUNSUPPORTED;
+  }
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev != H->device) {
+    (void)hipGetLastError();
+    hm::set_error("count_exact_noalloc: the graph lives on device %d, the current device is %d", H->device, dev);
+    return HM_EINVAL;
+  }
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  unsigned long long* s = nullptr;
+  HM_TRY(hm::noalloc_scratch(dev, &s));
+  hm::note_use(H, st);
+  const hm::ClassTables& t = hm::class_tables();
+  hm::LutArg luts;
+  std::memcpy(luts.b, t.lut4, 2048);
+  std::memcpy(luts.b + 2048, t.lut3, 16);
+  hm::k_noalloc_prepare<<<16, 256, 0, st>>>(s, luts);
+  HM_HIP(hipGetLastError());
+  const uint8_t* lut = reinterpret_cast<const uint8_t*>(s + hm::kNoAllocHistWords) + (k == 4 ? 0 : 2048);
+  hm::launch_bits_count(H, k, lut, s, st);
+  HM_HIP(hipGetLastError());
+  hm::k_combine<<<1, 256, 0, st>>>(s, t.n_classes[k], hm::pairs_only_mask(k), counts);
+  HM_HIP(hipGetLastError());
+  return HM_OK;
 }
