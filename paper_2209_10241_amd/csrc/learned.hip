@@ -375,18 +375,33 @@ __global__ void __launch_bounds__(kThreads) k_mlp_train(const float* __restrict_
   }
 }
 
-// grad[p] = sum over wavefronts of partial[w][p] (fixed order); p = kNParams is the loss
-__global__ void k_reduce_partials(const float* __restrict__ partial, uint32_t n_waves, float* __restrict__ grad) {
-  const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p > uint32_t(kNParams)) return;
+// grad[p] = sum over wavefronts of partial[w][p]; p = kNParams is the loss.
+// Workgroups of four wavefronts take 64 consecutive parameters: wavefront q
+// sums rows w = q, q + 4, ... and the four sums are added in the order
+// q = 0..3, so the order of every addition is fixed.
+constexpr uint32_t kReduceParams = kWave;
+__global__ void __launch_bounds__(kThreads) k_reduce_partials(const float* __restrict__ partial, uint32_t n_waves,
+                                                              float* __restrict__ grad) {
+  __shared__ float part[kWavesPerBlock][kReduceParams];
+  const uint32_t lane = threadIdx.x & (kWave - 1), q = threadIdx.x / kWave;
+  const uint32_t p = blockIdx.x * kReduceParams + lane;
   float s = 0.f;
-  for (uint32_t w = 0; w < n_waves; ++w) s += partial[uint64_t(w) * (kNParams + 1) + p];
-  grad[p] = s;
+  if (p <= uint32_t(kNParams))
+    for (uint32_t w = q; w < n_waves; w += kWavesPerBlock) s += partial[uint64_t(w) * (kNParams + 1) + p];
+  part[q][lane] = s;
+  __syncthreads();
+  if (q == 0 && p <= uint32_t(kNParams)) {
+    float t = part[0][lane];
+    for (uint32_t r = 1; r < kWavesPerBlock; ++r) t += part[r][lane];
+    grad[p] = t;
+  }
 }
 
+// One Adam step; thread 0 also keeps the step's loss (grad[kNParams]) at loss[0].
 __global__ void k_adam(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m, float* __restrict__ v,
-                       float lr, float b1, float b2, float eps, float c1, float c2) {
+                       float lr, float b1, float b2, float eps, float c1, float c2, float* __restrict__ loss) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0) loss[0] = g[kNParams];
   if (i >= kNParams) return;
   const float gi = g[i];
   const float mi = b1 * m[i] + (1.f - b1) * gi;
@@ -841,7 +856,8 @@ int hm_mlp_grad(const float* params, const float* x, const float* t, uint64_t n,
   float* partial = nullptr;
   HM_TRY(tmp.get(&partial, uint64_t(waves) * (hm::kNParams + 1)));
   hm::k_mlp_train<<<blocks, hm::kThreads, 0, st>>>(params, x, t, n, n ? 1.f / float(n) : 0.f, partial);
-  hm::k_reduce_partials<<<(hm::kNParams + 256) / 256, 256, 0, st>>>(partial, waves, grad);
+  hm::k_reduce_partials<<<(hm::kNParams + hm::kReduceParams) / hm::kReduceParams, hm::kThreads, 0, st>>>(partial, waves,
+                                                                                                     grad);
   HM_HIP(hipGetLastError());
   HM_HIP(hipStreamSynchronize(st));
   return HM_OK;
@@ -938,29 +954,36 @@ int hm_model_train(const hm_graph* H, int k, const hm_train_opts* opts, hm_model
     if (rc == HM_OK && hipStreamSynchronize(st) != hipSuccess) rc = HM_EDEVICE;
     for (int s = 0; s < ns; ++s) M->tstd[s] = host_stats[2 * s + 1] > 0.f ? 1.f / host_stats[2 * s + 1] : 1.f;
   }
-  // Adam over mini-batches
+  // Adam over mini-batches; every step's loss stays on the device and an
+  // epoch's losses are read back once, at its end
   int step = 0;
   const float b1 = 0.9f, b2 = 0.999f;
+  const uint64_t batches_per_epoch = n ? (n + batch - 1) / batch : 0;
+  float* losses = nullptr;
+  if (rc == HM_OK) rc = tmp.get(&losses, batches_per_epoch + 1);
+  std::vector<float> host_losses(batches_per_epoch + 1);
   for (int ep = 0; ep < opts->epochs && rc == HM_OK && n; ++ep) {
-    double ep_loss = 0.0;
-    int n_batches = 0;
+    uint64_t n_batches = 0;
     for (uint64_t b0 = 0; b0 < n && rc == HM_OK; b0 += batch) {
       const uint64_t nb = std::min<uint64_t>(batch, n - b0);
       hm::k_mlp_train<<<blocks, hm::kThreads, 0, st>>>(M->params, Xp + b0 * hm::kF, tp + b0, nb, 1.f / float(nb),
                                                        partial);
-      hm::k_reduce_partials<<<(hm::kNParams + 256) / 256, 256, 0, st>>>(partial, waves, grad);
+      hm::k_reduce_partials<<<(hm::kNParams + hm::kReduceParams) / hm::kReduceParams, hm::kThreads, 0, st>>>(
+          partial, waves, grad);
       ++step;
       const float c1 = 1.f - std::pow(b1, float(step)), c2 = 1.f - std::pow(b2, float(step));
-      hm::k_adam<<<(hm::kNParams + 255) / 256, 256, 0, st>>>(M->params, grad, m, v, opts->lr, b1, b2, 1e-8f, c1, c2);
+      hm::k_adam<<<(hm::kNParams + 255) / 256, 256, 0, st>>>(M->params, grad, m, v, opts->lr, b1, b2, 1e-8f, c1, c2,
+                                                              losses + n_batches);
       if (hipGetLastError() != hipSuccess) rc = HM_EDEVICE;
-      float l = 0.f;
-      if (rc == HM_OK && hipMemcpyAsync(&l, grad + hm::kNParams, sizeof(float), hipMemcpyDeviceToHost, st) != hipSuccess)
-        rc = HM_EDEVICE;
-      if (rc == HM_OK && hipStreamSynchronize(st) != hipSuccess) rc = HM_EDEVICE;
-      ep_loss += l;
       ++n_batches;
     }
-    M->loss.push_back(float(ep_loss / std::max(1, n_batches)));
+    if (rc == HM_OK && hipMemcpyAsync(host_losses.data(), losses, sizeof(float) * n_batches, hipMemcpyDeviceToHost,
+                                      st) != hipSuccess)
+      rc = HM_EDEVICE;
+    if (rc == HM_OK && hipStreamSynchronize(st) != hipSuccess) rc = HM_EDEVICE;
+    double ep_loss = 0.0;
+    for (uint64_t i = 0; i < n_batches; ++i) ep_loss += host_losses[i];
+    M->loss.push_back(float(ep_loss / double(std::max<uint64_t>(1, n_batches))));
   }
   if (rc != HM_OK) {
     hm::dfree(M->params);
