@@ -253,6 +253,57 @@ int count_sampled_indices(const hm_graph* H, int k, const uint32_t* idx2, uint64
 int count_nulls(const hm_graph* H, int k, int n_rand, uint64_t seed, int64_t* real, int64_t* nulls, float* z,
                 void* stream);
 
+/* Null models of count_nulls_model:
+ *   HM_NULL_STUBS   stub matching with local repair (count_nulls' model)
+ *   HM_NULL_CONFIG  the configuration model of Section 6.3 (Chodrow, J.
+ *                   Complex Networks 2020), sampled by Markov chain Monte
+ *                   Carlo: copy c starts from H's unique hyperedges of size
+ *                   >= 2 (first-occurrence order) and runs `sweeps` rounds;
+ *                   round r orders the hyperedges by (word 0 of Philox4x64-10
+ *                   at counter (i, r, 0, 0), i) under key (seed, (5 << 32) |
+ *                   c), pairs them two by two, and reshuffles each pair e, f:
+ *                   shared nodes stay in both, the others (e - f then f - e,
+ *                   ascending) are dealt out by a partial Fisher-Yates shuffle
+ *                   (draw q: q + hi64(w (|D| - q)), w = word q mod 4 at counter
+ *                   (t, r, 1 + q div 4, 0) for pair t) keeping both sizes.
+ * Both keep every node degree and hyperedge size and repeat no node inside a
+ * hyperedge; a copy may hold one node set twice, which counting collapses. */
+#define HM_NULL_STUBS 0
+#define HM_NULL_CONFIG 1
+
+/* count_nulls with a choice of null model; sweeps (1..4096) is the number of
+ * reshuffle rounds of HM_NULL_CONFIG and is ignored for HM_NULL_STUBS.  The
+ * same batched, graph-captured pipeline as count_nulls (a call with another
+ * model, order or copy count re-plans it).  Errors as count_nulls, and
+ * HM_EINVAL for an unknown model or sweeps out of range. */
+int count_nulls_model(const hm_graph* H, int k, int n_rand, int model, int sweeps, uint64_t seed, int64_t* real,
+                      int64_t* nulls, float* z, void* stream);
+
+/* Null copy `copy` of count_nulls_model's model, as hm_null_export. */
+int hm_null_export_model(const hm_graph* H, int model, int sweeps, uint64_t seed, uint32_t copy, uint32_t* members,
+                         uint64_t* offsets);
+
+/* Motif profile (Section 6.3: observed frequencies against a null model;
+ * the relative abundance of the cited higher-order motif work):
+ *   delta_m = (x_m - mu_m) / (x_m + mu_m + eps),  mu_m the mean of the n_rand
+ *   null rows, and the significance profile sp = delta / ||delta||_2 (zeros
+ *   when delta is zero).
+ * real: device double [n_classes] (exact counts or estimates); nulls: device
+ * double [n_rand][n_classes]; delta, sp: device double [n_classes] outputs,
+ * either may be NULL.  fp64 throughout.  Asynchronous on `stream`.
+ * Errors: HM_EINVAL for NULL inputs (or both outputs NULL), n_rand < 1,
+ * n_classes outside [1, 65536] or eps < 0. */
+int hm_motif_profile(const double* real, const double* nulls, int n_rand, int n_classes, double eps, double* delta,
+                     double* sp, void* stream);
+
+/* Accuracy of an estimated profile against the exact one (Section 6.3,
+ * Table 3): out3 (device double [3]) receives Pearson's correlation rho, the
+ * largest absolute error MaxAE and the mean absolute error MAE over the
+ * n_classes values (est, exact: device double).  rho is 0 when either profile
+ * is constant.  Asynchronous on `stream`.
+ * Errors: HM_EINVAL for a NULL argument or n_classes outside [1, 65536]. */
+int hm_profile_quality(const double* est, const double* exact, int n_classes, double* out3, void* stream);
+
 /* Items per tile chosen for the last count_nulls on H (host array of 3:
  * 3-node hyperedges, pairs, hyperedges of size k); HM_EINVAL before any. */
 int hm_null_tile_sizes(const hm_graph* H, uint32_t* out3);

@@ -4,6 +4,7 @@ from .binding import (  # noqa: F401
     HM_ALLOC_PAPER, HM_ALLOC_PROPORTIONAL, HM_OPT_BITSET_MAX_NODES, HM_OPT_HUB_MIN_DEGREE, HM_OPT_ONE_PASS_MAX_EDGES,
     HM_OPT_SAMPLE_CHUNK_SCALE, count_nulls, count_sampled, count_sampled_indices,
     hm_null_export, hm_null_tile_sizes,
+    HM_NULL_CONFIG, HM_NULL_STUBS, count_nulls_model, hm_motif_profile, hm_null_export_model, hm_profile_quality,
     Model, count_sampled_learned, count_sampled_weighted_indices, hm_contrib, hm_features, hm_mlp_forward,
     hm_mlp_grad, hm_model_train, hm_proposal_probs,
     hm_get_option, hm_sample_draw, hm_sample_sizes, hm_sample_sizes_for, hm_set_option,

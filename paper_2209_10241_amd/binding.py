@@ -29,6 +29,8 @@ HM_OPT_ONE_PASS_MAX_EDGES = 3
 HM_OPT_HUB_MIN_DEGREE = 4
 HM_ALLOC_PROPORTIONAL = 0
 HM_ALLOC_PAPER = 1
+HM_NULL_STUBS = 0
+HM_NULL_CONFIG = 1
 
 _ERROR_NAMES = {HM_EINVAL: "HM_EINVAL", HM_EUNSUPPORTED: "HM_EUNSUPPORTED", HM_ENOMEM: "HM_ENOMEM",
                 HM_EDEVICE: "HM_EDEVICE", HM_EINTERNAL: "HM_EINTERNAL"}
@@ -72,7 +74,11 @@ SIGNATURES = {
     "count_sampled": (_int, [_vp, _int, _dbl, _u64, _int, _vp, _vp, _vp]),
     "count_sampled_indices": (_int, [_vp, _int, _vp, _u64, _vp, _u64, _vp, _u64, _vp, _vp, _vp]),
     "count_nulls": (_int, [_vp, _int, _int, _u64, _vp, _vp, _vp, _vp]),
+    "count_nulls_model": (_int, [_vp, _int, _int, _int, _int, _u64, _vp, _vp, _vp, _vp]),
     "hm_null_export": (_int, [_vp, _u64, _u32, _vp, _vp]),
+    "hm_null_export_model": (_int, [_vp, _int, _int, _u64, _u32, _vp, _vp]),
+    "hm_motif_profile": (_int, [_vp, _vp, _int, _int, _dbl, _vp, _vp, _vp]),
+    "hm_profile_quality": (_int, [_vp, _vp, _int, _vp, _vp]),
     "hm_null_tile_sizes": (_int, [_vp, _vp]),
     "hm_features": (_int, [_vp, _int, _vp, _vp]),
     "hm_contrib": (_int, [_vp, _int, _vp, _vp]),
@@ -376,6 +382,53 @@ def hm_null_export(H: Graph, seed: int, copy: int):
     _check(lib().hm_null_export(H.handle, int(seed) & (2**64 - 1), copy, members.ctypes.data_as(ctypes.c_void_p),
                                 offsets.ctypes.data_as(ctypes.c_void_p)))
     return members[:st["n_unique_members"]], offsets
+
+
+def count_nulls_model(H: Graph, k: int, n_rand: int, model: int, sweeps: int, seed: int, stream=None):
+    """count_nulls under a chosen null model (HM_NULL_STUBS or HM_NULL_CONFIG)."""
+    import torch
+    n = hm_num_classes(k)
+    real = torch.empty(n, dtype=torch.int64, device="cuda")
+    nulls = torch.empty((n_rand, n), dtype=torch.int64, device="cuda")
+    z = torch.empty(n, dtype=torch.float32, device="cuda")
+    _check(lib().count_nulls_model(H.handle, k, n_rand, model, sweeps, int(seed) & (2**64 - 1),
+                                   ctypes.c_void_p(real.data_ptr()), ctypes.c_void_p(nulls.data_ptr()),
+                                   ctypes.c_void_p(z.data_ptr()), _stream_ptr(stream)))
+    return real, nulls, z
+
+
+def hm_null_export_model(H: Graph, model: int, sweeps: int, seed: int, copy: int):
+    """(members uint32, offsets uint64) numpy arrays of one copy of the chosen null model."""
+    st = H.stats()
+    members = np.zeros(max(1, st["n_unique_members"]), dtype=np.uint32)
+    offsets = np.zeros(st["n_unique"] + 1, dtype=np.uint64)
+    _check(lib().hm_null_export_model(H.handle, model, sweeps, int(seed) & (2**64 - 1), copy,
+                                      members.ctypes.data_as(ctypes.c_void_p),
+                                      offsets.ctypes.data_as(ctypes.c_void_p)))
+    return members[:st["n_unique_members"]], offsets
+
+
+def hm_motif_profile(real, nulls, eps: float = 4.0, stream=None):
+    """(delta, sp) float64 tensors: relative abundance against the null rows and its normalised form."""
+    import torch
+    real = torch.as_tensor(real).to(device="cuda", dtype=torch.float64).contiguous()
+    nulls = torch.as_tensor(nulls).to(device="cuda", dtype=torch.float64).contiguous()
+    C = real.numel()
+    delta = torch.empty(C, dtype=torch.float64, device="cuda")
+    sp = torch.empty(C, dtype=torch.float64, device="cuda")
+    _check(lib().hm_motif_profile(_ptr(real), _ptr(nulls), nulls.shape[0], C, float(eps), _ptr(delta), _ptr(sp),
+                                  _stream_ptr(stream)))
+    return delta, sp
+
+
+def hm_profile_quality(est, exact, stream=None):
+    """(rho, MaxAE, MAE) of an estimated profile against the exact one."""
+    import torch
+    est = torch.as_tensor(est).to(device="cuda", dtype=torch.float64).contiguous()
+    exact = torch.as_tensor(exact).to(device="cuda", dtype=torch.float64).contiguous()
+    out = torch.empty(3, dtype=torch.float64, device="cuda")
+    _check(lib().hm_profile_quality(_ptr(est), _ptr(exact), est.numel(), _ptr(out), _stream_ptr(stream)))
+    return tuple(float(x) for x in out.cpu().tolist())
 
 
 def hm_null_tile_sizes(H: Graph):

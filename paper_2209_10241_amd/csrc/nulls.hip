@@ -15,6 +15,20 @@
 //            (word0 of counter (t, r, 0, 0), t) and dealt back in that order.
 // Each copy is then counted exactly and z_m = (x_m - mean_m) / sd_m over the
 // copies (sd with n - 1) is formed in fp64 and rounded to fp32.
+//
+// Configuration model (Section 6.3's null; Chodrow, J. Complex Networks 2020):
+// Markov chain Monte Carlo with pairwise reshuffles, which keep degrees and
+// sizes and whose symmetric moves keep the uniform distribution.  Copy c
+// starts from the input's hyperedges and runs `sweeps` rounds with the key
+// (seed, 5<<32 | c):
+//   round r  order the hyperedges by (word0 of counter (i, r, 0, 0), i) into
+//            pi; pair t = (pi[2t], pi[2t+1]); an odd last hyperedge waits;
+//   pair t   I = e & f; D = (e - f ascending) then (f - e ascending);
+//            a = |e - f|; for q < a: j = q + hi64(w (|D| - q)), w = word
+//            (q mod 4) of counter (t, r, 1 + q div 4, 0); swap D[q], D[j];
+//            e = sort(I + D[:a]), f = sort(I + D[a:]).
+// The motif profile is the relative abundance (x - mu) / (x + mu + eps) of the
+// cited higher-order motif work, with its significance profile.
 #include <vector>
 
 #include <map>
@@ -52,6 +66,207 @@ __global__ void k_null_gather(const uint32_t* __restrict__ vals, uint64_t n, uin
   for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += uint64_t(gridDim.x) * blockDim.x) {
     const uint64_t c = i / T;
     members[i] = stubs[vals[i] - c * T];
+  }
+}
+
+// ---------------------------------------------------------------- configuration model
+constexpr unsigned long long kDomainConfig = 5ull;
+
+// members of every copy := the input's (R x T)
+__global__ void k_cfg_init(uint32_t R, uint64_t T, const uint32_t* __restrict__ src, uint32_t* __restrict__ members) {
+  const uint64_t n = uint64_t(R) * T;
+  for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += uint64_t(gridDim.x) * blockDim.x)
+    members[i] = src[i % T];
+}
+
+// round r's key of hyperedge i of copy c0 + c; vals = c * E + i
+__global__ void k_cfg_keys(uint32_t c0, uint32_t R, uint32_t E, uint32_t r, const unsigned long long* __restrict__ seed_p,
+                           unsigned long long* keys, uint32_t* vals) {
+  const unsigned long long seed = *seed_p;
+  const uint64_t n = uint64_t(R) * E;
+  for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += uint64_t(gridDim.x) * blockDim.x) {
+    const uint64_t c = i / E, e = i % E;
+    keys[i] = philox4x64_10(e, r, 0, 0, seed, (kDomainConfig << 32) | (c0 + c)).v[0];
+    vals[i] = uint32_t(i);
+  }
+}
+
+// One thread per (copy, pair): the pairwise reshuffle of the two hyperedges
+// the sorted order pairs.  members holds copy c's hyperedges at c * T +
+// off[e]; tmp (R x T) gives each pair the slots of its two hyperedges as
+// working space: virtual slot q < |e| is tmp[c*T + off[e] + q], the rest
+// tmp[c*T + off[f] + q - |e|].  D takes slots [0, |D|), I the last |I|.
+__global__ void k_cfg_pairs(uint32_t c0, uint32_t R, uint32_t E, uint64_t T, uint32_t r,
+                            const unsigned long long* __restrict__ seed_p, const uint32_t* __restrict__ order,
+                            const unsigned long long* __restrict__ off, uint32_t* __restrict__ members,
+                            uint32_t* __restrict__ tmp) {
+  const unsigned long long seed = *seed_p;
+  const uint32_t P = E / 2;
+  const uint64_t n = uint64_t(R) * P;
+  for (uint64_t it = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; it < n; it += uint64_t(gridDim.x) * blockDim.x) {
+    const uint32_t c = uint32_t(it / P), t = uint32_t(it % P);
+    const uint64_t base = uint64_t(c) * T;
+    const uint32_t ie = order[uint64_t(c) * E + 2 * t] - c * E, jf = order[uint64_t(c) * E + 2 * t + 1] - c * E;
+    const uint64_t oe = off[ie], of = off[jf];
+    const uint32_t se = uint32_t(off[ie + 1] - oe), sf = uint32_t(off[jf + 1] - of);
+    uint32_t* me = members + base + oe;
+    uint32_t* mf = members + base + of;
+    uint32_t* te = tmp + base + oe;
+    uint32_t* tf = tmp + base + of;
+    auto slot = [&](uint32_t q) -> uint32_t& { return q < se ? te[q] : tf[q - se]; };
+    // two merges of the ascending lists: e - f into D and e & f into I, then
+    // f - e after e - f
+    uint32_t nd = 0, ni = 0;
+    const uint32_t total = se + sf;
+    for (uint32_t x = 0, y = 0; x < se;) {
+      if (y == sf || me[x] < mf[y]) {
+        slot(nd++) = me[x++];
+      } else if (mf[y] < me[x]) {
+        ++y;
+      } else {
+        slot(total - 1 - ni++) = me[x];
+        ++x;
+        ++y;
+      }
+    }
+    const uint32_t a = nd;   // |e - f|
+    for (uint32_t x = 0, y = 0; y < sf;) {
+      if (x == se || mf[y] < me[x]) {
+        slot(nd++) = mf[y++];
+      } else if (me[x] < mf[y]) {
+        ++x;
+      } else {
+        ++x;
+        ++y;
+      }
+    }
+    Philox4 w{{0, 0, 0, 0}};
+    for (uint32_t q = 0; q < a; ++q) {
+      if ((q & 3) == 0) w = philox4x64_10(t, r, 1 + q / 4, 0, seed, (kDomainConfig << 32) | (c0 + c));
+      const uint32_t j = q + uint32_t(bounded64(w.v[q & 3], nd - q));
+      const uint32_t tq = slot(q);
+      slot(q) = slot(j);
+      slot(j) = tq;
+    }
+    // e = sort(I + D[:a]), f = sort(I + D[a:]) (insertion sorts into place)
+    auto place = [&](uint32_t* out, uint32_t lo, uint32_t hi) {
+      uint32_t m = 0;
+      for (uint32_t u = 0; u < ni; ++u) {
+        const uint32_t v = slot(total - 1 - u);
+        uint32_t k = m++;
+        while (k > 0 && out[k - 1] > v) {
+          out[k] = out[k - 1];
+          --k;
+        }
+        out[k] = v;
+      }
+      for (uint32_t q = lo; q < hi; ++q) {
+        const uint32_t v = slot(q);
+        uint32_t k = m++;
+        while (k > 0 && out[k - 1] > v) {
+          out[k] = out[k - 1];
+          --k;
+        }
+        out[k] = v;
+      }
+    };
+    place(me, 0, a);
+    place(mf, a, nd);
+  }
+}
+
+// delta_m = (x_m - mu_m) / (x_m + mu_m + eps) over R null rows, and the
+// significance profile delta / ||delta||_2 (one workgroup, fp64)
+__global__ void k_motif_profile(const double* __restrict__ real, const double* __restrict__ nulls, uint32_t R, int C,
+                                double eps, double* __restrict__ delta, double* __restrict__ sp) {
+  __shared__ double red[256];
+  double own = 0.0, sq = 0.0;
+  for (int c = threadIdx.x; c < C; c += blockDim.x) {
+    double s = 0.0;
+    for (uint32_t i = 0; i < R; ++i) s += nulls[uint64_t(i) * C + c];
+    const double mu = s / double(R), x = real[c];
+    own = (x - mu) / (x + mu + eps);
+    if (delta) delta[c] = own;
+    sq += own * own;
+  }
+  red[threadIdx.x] = sq;
+  __syncthreads();
+  for (int d = 128; d > 0; d >>= 1) {
+    if (int(threadIdx.x) < d) red[threadIdx.x] += red[threadIdx.x + d];
+    __syncthreads();
+  }
+  const double norm = sqrt(red[0]);
+  if (sp)
+    for (int c = threadIdx.x; c < C; c += blockDim.x) {
+      double s = 0.0;
+      for (uint32_t i = 0; i < R; ++i) s += nulls[uint64_t(i) * C + c];
+      const double mu = s / double(R), x = real[c];
+      const double d = (x - mu) / (x + mu + eps);
+      sp[c] = norm > 0.0 ? d / norm : 0.0;
+    }
+}
+
+// Pearson's rho, the largest and the mean absolute error between two
+// profiles of C values (one workgroup of 256, fp64, fixed summation order)
+__global__ void k_profile_quality(const double* __restrict__ a, const double* __restrict__ b, int C,
+                                  double* __restrict__ out) {
+  __shared__ double r0[256], r1[256], r2[256];
+  double sa = 0.0, sb = 0.0;
+  for (int c = threadIdx.x; c < C; c += blockDim.x) {
+    sa += a[c];
+    sb += b[c];
+  }
+  r0[threadIdx.x] = sa;
+  r1[threadIdx.x] = sb;
+  __syncthreads();
+  for (int d = 128; d > 0; d >>= 1) {
+    if (int(threadIdx.x) < d) {
+      r0[threadIdx.x] += r0[threadIdx.x + d];
+      r1[threadIdx.x] += r1[threadIdx.x + d];
+    }
+    __syncthreads();
+  }
+  const double ma = r0[0] / double(C), mb = r1[0] / double(C);
+  __syncthreads();
+  double sab = 0.0, saa = 0.0, sbb = 0.0, mx = 0.0, sabs = 0.0;
+  for (int c = threadIdx.x; c < C; c += blockDim.x) {
+    const double da = a[c] - ma, db = b[c] - mb;
+    sab += da * db;
+    saa += da * da;
+    sbb += db * db;
+    const double e = fabs(a[c] - b[c]);
+    mx = fmax(mx, e);
+    sabs += e;
+  }
+  r0[threadIdx.x] = sab;
+  r1[threadIdx.x] = saa;
+  r2[threadIdx.x] = sbb;
+  __syncthreads();
+  for (int d = 128; d > 0; d >>= 1) {
+    if (int(threadIdx.x) < d) {
+      r0[threadIdx.x] += r0[threadIdx.x + d];
+      r1[threadIdx.x] += r1[threadIdx.x + d];
+      r2[threadIdx.x] += r2[threadIdx.x + d];
+    }
+    __syncthreads();
+  }
+  const double s_ab = r0[0], s_aa = r1[0], s_bb = r2[0];
+  __syncthreads();
+  r0[threadIdx.x] = mx;
+  r1[threadIdx.x] = sabs;
+  __syncthreads();
+  for (int d = 128; d > 0; d >>= 1) {
+    if (int(threadIdx.x) < d) {
+      r0[threadIdx.x] = fmax(r0[threadIdx.x], r0[threadIdx.x + d]);
+      r1[threadIdx.x] += r1[threadIdx.x + d];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double den = sqrt(s_aa * s_bb);
+    out[0] = den > 0.0 ? s_ab / den : 0.0;
+    out[1] = r0[0];
+    out[2] = r1[0] / double(C);
   }
 }
 
@@ -680,6 +895,8 @@ __global__ void k_b_combine(const unsigned long long* __restrict__ hist_all, int
 // ---------------------------------------------------------------- plan
 struct NullPlan {
   int k = 0;
+  int model = HM_NULL_STUBS, sweeps = 0;
+  uint32_t* cfg_tmp = nullptr;   // working slots of the configuration model (R x T)
   uint32_t R = 0, E = 0, N = 0;
   uint64_t T = 0, n2H = 0, n3H = 0, n4H = 0;
   int B = 0;
@@ -764,7 +981,7 @@ BatchView batch_view(const NullPlan& P) {
   return b;
 }
 
-int make_plan(const hm_graph* H, int k, uint32_t R, NullPlan** out) {
+int make_plan(const hm_graph* H, int k, uint32_t R, int model, int sweeps, NullPlan** out) {
   NullPlan* P = new (std::nothrow) NullPlan();
   if (!P) {
     set_error("host allocation failed");
@@ -772,6 +989,8 @@ int make_plan(const hm_graph* H, int k, uint32_t R, NullPlan** out) {
   }
   P->k = k;
   P->R = R;
+  P->model = model;
+  P->sweeps = sweeps;
   P->E = uint32_t(H->n_unique);
   P->T = H->n_unique_members;
   P->N = H->n_nodes;
@@ -801,6 +1020,7 @@ int make_plan(const hm_graph* H, int k, uint32_t R, NullPlan** out) {
   if (rc == HM_OK) rc = P->get(&(ptr), (n))
   GET(P->seed, 1);
   GET(P->members, RT);
+  if (model == HM_NULL_CONFIG) GET(P->cfg_tmp, RT);
   GET(P->skeys, RT);
   GET(P->skeys_tmp, RT);
   GET(P->svals, RT);
@@ -884,6 +1104,32 @@ int enqueue_stubs(const hm_graph* H, NullPlan& P, uint32_t c0, hipStream_t st) {
   k_null_repair<<<P.repair_blocks, kThreads, 0, st>>>(c0, P.R, P.E, P.T, H->all_off, P.members, P.seed, P.rs,
                                                       P.failed);
   HM_HIP(hipGetLastError());
+  return HM_OK;
+}
+
+// Configuration-model copies c0 .. c0+R-1 into P.members (no allocation, no
+// sync): every copy starts from the input and runs P.sweeps rounds of
+// pairwise reshuffles.
+int enqueue_config(const hm_graph* H, NullPlan& P, uint32_t c0, hipStream_t st) {
+  const uint64_t n = uint64_t(P.R) * P.T, ne = uint64_t(P.R) * P.E;
+  HM_TRY(fill_u32(P.failed, 0, 1, st));
+  if (n == 0) return HM_OK;
+  k_cfg_init<<<grid_for(n), 256, 0, st>>>(P.R, P.T, H->all_members, P.members);
+  HM_HIP(hipGetLastError());
+  if (P.E < 2) return HM_OK;
+  for (int r = 0; r < P.sweeps; ++r) {
+    k_cfg_keys<<<grid_for(ne), 256, 0, st>>>(c0, P.R, P.E, uint32_t(r), P.seed, P.skeys, P.svals);
+    HM_HIP(hipGetLastError());
+    HM_TRY(radix_sort_ws(P.skeys, P.svals, P.skeys_tmp, P.svals_tmp, ne, 64, P.sort_ws, st));
+    if (P.R > 1) {
+      k_copy_of<<<grid_for(ne), 256, 0, st>>>(P.svals, ne, P.E, P.skeys);
+      HM_HIP(hipGetLastError());
+      HM_TRY(radix_sort_ws(P.skeys, P.svals, P.skeys_tmp, P.svals_tmp, ne, bits_for(P.R), P.sort_ws, st));
+    }
+    k_cfg_pairs<<<grid_for(uint64_t(P.R) * (P.E / 2)), 256, 0, st>>>(c0, P.R, P.E, P.T, uint32_t(r), P.seed, P.svals,
+                                                                    H->all_off, P.members, P.cfg_tmp);
+    HM_HIP(hipGetLastError());
+  }
   return HM_OK;
 }
 
@@ -979,8 +1225,12 @@ int enqueue_count(const hm_graph* H, NullPlan& P, const Chunks& ch, hipStream_t 
 
 // The seed-dependent part of a call (the real counts in P.real do not depend
 // on it and are counted once, before capture).
+int enqueue_copies(const hm_graph* H, NullPlan& P, uint32_t c0, hipStream_t st) {
+  return P.model == HM_NULL_CONFIG ? enqueue_config(H, P, c0, st) : enqueue_stubs(H, P, c0, st);
+}
+
 int enqueue_all(const hm_graph* H, NullPlan& P, hipStream_t st) {
-  HM_TRY(enqueue_stubs(H, P, 0, st));
+  HM_TRY(enqueue_copies(H, P, 0, st));
   HM_TRY(enqueue_ingest(H, P, st));
   HM_TRY(enqueue_count(H, P, P.chunks, st));
   const int C = class_tables().n_classes[P.k];
@@ -1045,10 +1295,13 @@ int autotune(const hm_graph* H, NullPlan& P, hipStream_t st) {
 }  // namespace
 
 // Generate copies [c0, c0 + R) into members (R x T, device), synchronously.
-int null_copies(const hm_graph* H, uint32_t c0, uint32_t R, uint64_t seed, uint32_t* members, hipStream_t st) {
+int null_copies(const hm_graph* H, uint32_t c0, uint32_t R, uint64_t seed, uint32_t* members, hipStream_t st,
+                int model, int sweeps) {
   note_use(H, st);
   if (H->n_unique_members == 0 || R == 0) return HM_OK;
   NullPlan P;
+  P.model = model;
+  P.sweeps = sweeps;
   P.R = R;
   P.E = uint32_t(H->n_unique);
   P.T = H->n_unique_members;
@@ -1073,10 +1326,11 @@ int null_copies(const hm_graph* H, uint32_t c0, uint32_t R, uint64_t seed, uint3
   HM_TRY(P.get(&P.rs.aux, uint64_t(P.repair_blocks) * P.rs.pool_pad));
   HM_TRY(P.get(&P.rs.val, uint64_t(P.repair_blocks) * P.rs.pool_pad));
   HM_TRY(P.get(&P.failed, 1));
+  if (model == HM_NULL_CONFIG) HM_TRY(P.get(&P.cfg_tmp, RT));
   P.members = members;
   unsigned long long s = seed;
   HM_HIP(hipMemcpyAsync(P.seed, &s, sizeof(s), hipMemcpyHostToDevice, st));
-  HM_TRY(enqueue_stubs(H, P, c0, st));
+  HM_TRY(enqueue_copies(H, P, c0, st));
   uint32_t host_failed = 0;
   HM_HIP(hipMemcpyAsync(&host_failed, P.failed, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
   HM_HIP(hipStreamSynchronize(st));
@@ -1087,8 +1341,8 @@ int null_copies(const hm_graph* H, uint32_t c0, uint32_t R, uint64_t seed, uint3
   return HM_OK;
 }
 
-int count_nulls_impl(hm_graph* H, int k, uint32_t R, uint64_t seed, int64_t* real, int64_t* nulls, float* z,
-                     hipStream_t st) {
+int count_nulls_impl(hm_graph* H, int k, uint32_t R, int model, int sweeps, uint64_t seed, int64_t* real,
+                     int64_t* nulls, float* z, hipStream_t st) {
   note_use(H, st);
   const int C = class_tables().n_classes[k];
   const uint8_t *lut4 = nullptr, *lut3 = nullptr;
@@ -1101,19 +1355,19 @@ int count_nulls_impl(hm_graph* H, int k, uint32_t R, uint64_t seed, int64_t* rea
     return HM_OK;
   }
   NullPlan* P = H->null_plan;
-  if (P && (P->k != k || P->R != R)) {
+  if (P && (P->k != k || P->R != R || P->model != model || P->sweeps != sweeps)) {
     destroy_null_plan(P);
     H->null_plan = P = nullptr;
   }
   if (!P) {
-    HM_TRY(make_plan(H, k, R, &P));
+    HM_TRY(make_plan(H, k, R, model, sweeps, &P));
     H->null_plan = P;
     // first run outside a graph: the real counts, then ingest the copies once
     // and tune the tile sizes
     HM_TRY(count_exact_impl(H, k, P->real, st));
     unsigned long long s0 = seed;
     HM_HIP(hipMemcpyAsync(P->seed, &s0, sizeof(s0), hipMemcpyHostToDevice, st));
-    HM_TRY(enqueue_stubs(H, *P, 0, st));
+    HM_TRY(enqueue_copies(H, *P, 0, st));
     HM_TRY(enqueue_ingest(H, *P, st));
     HM_TRY(autotune(H, *P, st));
     // capture the whole pipeline once; later calls replay it
@@ -1165,15 +1419,30 @@ int null_tuned_chunks(const hm_graph* H, uint32_t* out3) {
 
 extern "C" {
 
-int hm_null_export(const hm_graph* H, uint64_t seed, uint32_t copy, uint32_t* members, uint64_t* offsets) {
-  if (!H || !members || !offsets) {
-    hm::set_error("NULL argument to hm_null_export");
+static int null_model_args(int model, int sweeps) {
+  if (model != HM_NULL_STUBS && model != HM_NULL_CONFIG) {
+    hm::set_error("unknown null model %d", model);
     return HM_EINVAL;
   }
+  if (model == HM_NULL_CONFIG && (sweeps < 1 || sweeps > 4096)) {
+    hm::set_error("sweeps must be in [1, 4096] for the configuration model");
+    return HM_EINVAL;
+  }
+  return HM_OK;
+}
+
+int hm_null_export_model(const hm_graph* H, int model, int sweeps, uint64_t seed, uint32_t copy, uint32_t* members,
+                         uint64_t* offsets) {
+  if (!H || !members || !offsets) {
+    hm::set_error("NULL argument to hm_null_export_model");
+    return HM_EINVAL;
+  }
+  HM_TRY(null_model_args(model, sweeps));
   const uint64_t T = H->n_unique_members;
   void* buf = nullptr;
   HM_TRY(hm::dalloc(&buf, T * sizeof(uint32_t) + 4));
-  int rc = hm::null_copies(H, copy, 1, seed, static_cast<uint32_t*>(buf), nullptr);
+  int rc = hm::null_copies(H, copy, 1, seed, static_cast<uint32_t*>(buf), nullptr, model,
+                           model == HM_NULL_CONFIG ? sweeps : 0);
   if (rc == HM_OK && T) {
     if (hipMemcpy(members, buf, T * sizeof(uint32_t), hipMemcpyDeviceToHost) != hipSuccess) rc = HM_EDEVICE;
   }
@@ -1185,12 +1454,17 @@ int hm_null_export(const hm_graph* H, uint64_t seed, uint32_t copy, uint32_t* me
   return rc;
 }
 
-int count_nulls(const hm_graph* H, int k, int n_rand, uint64_t seed, int64_t* real, int64_t* nulls, float* z,
-                void* stream) {
+int hm_null_export(const hm_graph* H, uint64_t seed, uint32_t copy, uint32_t* members, uint64_t* offsets) {
+  return hm_null_export_model(H, HM_NULL_STUBS, 0, seed, copy, members, offsets);
+}
+
+int count_nulls_model(const hm_graph* H, int k, int n_rand, int model, int sweeps, uint64_t seed, int64_t* real,
+                      int64_t* nulls, float* z, void* stream) {
   if (!H || !nulls) {
     hm::set_error("NULL argument to count_nulls");
     return HM_EINVAL;
   }
+  HM_TRY(null_model_args(model, sweeps));
   if (k != 3 && k != 4) {
     hm::set_error("order %d is not supported (3 or 4)", k);
     return HM_EUNSUPPORTED;
@@ -1199,8 +1473,44 @@ int count_nulls(const hm_graph* H, int k, int n_rand, uint64_t seed, int64_t* re
     hm::set_error("n_rand must be in [2, 65535]");
     return HM_EINVAL;
   }
-  return hm::count_nulls_impl(const_cast<hm_graph*>(H), k, uint32_t(n_rand), seed, real, nulls, z,
+  return hm::count_nulls_impl(const_cast<hm_graph*>(H), k, uint32_t(n_rand), model,
+                              model == HM_NULL_CONFIG ? sweeps : 0, seed, real, nulls, z,
                               static_cast<hipStream_t>(stream));
+}
+
+int count_nulls(const hm_graph* H, int k, int n_rand, uint64_t seed, int64_t* real, int64_t* nulls, float* z,
+                void* stream) {
+  return count_nulls_model(H, k, n_rand, HM_NULL_STUBS, 0, seed, real, nulls, z, stream);
+}
+
+int hm_motif_profile(const double* real, const double* nulls, int n_rand, int n_classes, double eps, double* delta,
+                     double* sp, void* stream) {
+  if (!real || !nulls || (!delta && !sp)) {
+    hm::set_error("NULL argument to hm_motif_profile");
+    return HM_EINVAL;
+  }
+  if (n_rand < 1 || n_classes < 1 || n_classes > 65536 || !(eps >= 0.0)) {
+    hm::set_error("hm_motif_profile needs n_rand >= 1, 1 <= n_classes <= 65536 and eps >= 0");
+    return HM_EINVAL;
+  }
+  hm::k_motif_profile<<<1, 256, 0, static_cast<hipStream_t>(stream)>>>(real, nulls, uint32_t(n_rand), n_classes, eps,
+                                                                       delta, sp);
+  HM_HIP(hipGetLastError());
+  return HM_OK;
+}
+
+int hm_profile_quality(const double* est, const double* exact, int n_classes, double* out3, void* stream) {
+  if (!est || !exact || !out3) {
+    hm::set_error("NULL argument to hm_profile_quality");
+    return HM_EINVAL;
+  }
+  if (n_classes < 1 || n_classes > 65536) {
+    hm::set_error("n_classes must be in [1, 65536]");
+    return HM_EINVAL;
+  }
+  hm::k_profile_quality<<<1, 256, 0, static_cast<hipStream_t>(stream)>>>(est, exact, n_classes, out3);
+  HM_HIP(hipGetLastError());
+  return HM_OK;
 }
 
 int hm_null_tile_sizes(const hm_graph* H, uint32_t* out3) {
