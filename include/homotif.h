@@ -195,6 +195,14 @@ int hm_sample_sizes(const hm_graph* H, int k, double fraction, int allocation, u
  * unknown allocation; HM_EUNSUPPORTED for k other than 3 or 4. */
 int hm_sample_sizes_for(int k, const uint64_t* n_by_size, double fraction, int allocation, uint64_t* s_out);
 
+/* count_sampled with the number of draws of each stratum given (s2, s3, s4
+ * draws from the hyperedges of size 2, 3, 4; s4 is ignored when k = 3; a
+ * stratum with no hyperedge gets none).  Draws and estimator as
+ * count_sampled.  Errors: HM_EINVAL for a NULL argument or a size >= 2^31;
+ * HM_EUNSUPPORTED for k other than 3 or 4. */
+int count_sampled_sizes(const hm_graph* H, int k, uint64_t s2, uint64_t s3, uint64_t s4, uint64_t seed, float* est,
+                        int64_t* raw, void* stream);
+
 /* Write the drawn stratum indices (device uint32 arrays of S_2, S_3, S_4
  * values; pointers for empty strata may be NULL).  Draw i of stratum j is
  * hi64(w * |E_j|) with w the first word of Philox4x64-10 (Salmon et al.,
@@ -295,6 +303,23 @@ int hm_null_export_model(const hm_graph* H, int model, int sweeps, uint64_t seed
  * n_classes outside [1, 65536] or eps < 0. */
 int hm_motif_profile(const double* real, const double* nulls, int n_rand, int n_classes, double eps, double* delta,
                      double* sp, void* stream);
+
+/* The stratum-budget search of the appendix (Fig. 6): with S draws in total
+ * split S_2 : S_3 : S_4 = 1 : ratio3[i] : ratio4[j] (S_2 = llround(S / (1 +
+ * ratio3 + ratio4)), S_3 = min(S - S_2, llround(ratio3 S_2)), S_4 the rest;
+ * k = 3: S_3 = S - S_2 and ratio4 is unused), every cell runs `reps` sampled
+ * estimates (count_sampled_sizes with seeds seed, seed + 1, ...), forms each
+ * estimate's profile against the null rows (hm_motif_profile with eps) and
+ * its Pearson correlation with exact_profile (hm_profile_quality); rho
+ * (host double [n3 * n4], row i, column j) receives the mean correlation over
+ * the repetitions.  nulls: device double [n_rand][C]; exact_profile: device
+ * double [C].  Synchronous.
+ * Errors: HM_EINVAL for a NULL argument, S = 0 or >= 2^31, an empty grid or
+ * more than 4096 cells, reps outside [1, 1024], n_rand < 1, eps < 0 or a
+ * negative ratio; HM_EUNSUPPORTED for k other than 3 or 4. */
+int hm_stratum_search(const hm_graph* H, int k, uint64_t S, const double* ratio3, int n3, const double* ratio4, int n4,
+                      int reps, uint64_t seed, const double* nulls, int n_rand, const double* exact_profile, double eps,
+                      double* rho, void* stream);
 
 /* Accuracy of an estimated profile against the exact one (Section 6.3,
  * Table 3): out3 (device double [3]) receives Pearson's correlation rho, the

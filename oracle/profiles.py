@@ -16,6 +16,12 @@ draws; the significance profile is delta / ||delta||_2.  This reading is
 parity unpinned against the paper: its values are checked here only against
 their definition (hand-worked examples and properties).
 
+The stratum-budget search of the appendix (Fig. 6) splits S draws as
+S_2 : S_3 : S_4 = 1 : r3 : r4 and, over a grid of (r3, r4), keeps the mean
+Pearson correlation between estimated and exact profiles; it is composed of
+the pinned parts (Algorithm 4's estimator, the profile, rho) and the size
+rule, which is pinned by hand-worked values.
+
 The configuration model is sampled by Markov chain Monte Carlo with the
 pairwise reshuffle move of Chodrow (J. Complex Networks 2020): for two
 hyperedges e and f, the nodes they share stay in both, and the nodes in
@@ -44,7 +50,7 @@ import math
 import numpy as np
 
 from . import philox
-from .core import Normalised, normalise
+from .core import Normalised, normalise, sampled_raw, scale_estimate
 
 DOMAIN_CONFIG = 5
 EPS = 4.0
@@ -106,3 +112,43 @@ def quality(est_profile, exact_profile):
     rho = float(np.sum(da * db)) / den if den > 0 else 0.0
     err = np.abs(a - b)
     return rho, float(err.max()), float(err.mean())
+
+
+def _round_half_up(x: float) -> int:
+    return int(math.floor(x + 0.5))
+
+
+def stratum_sizes(S: int, r3: float, r4: float, k: int = 4) -> dict:
+    """S_2 : S_3 : S_4 = 1 : r3 : r4 with S_2 + S_3 + S_4 = S (appendix, Fig. 6):
+    S_2 = round(S / (1 + r3 + r4)), S_3 = min(S - S_2, round(r3 S_2)), S_4 the rest
+    (k = 3: S_3 = S - S_2), halves rounded up."""
+    s2 = _round_half_up(S / (1.0 + r3 + (r4 if k == 4 else 0.0)))
+    if k == 3:
+        return {2: s2, 3: S - s2}
+    s3 = min(S - s2, _round_half_up(r3 * s2))
+    return {2: s2, 3: s3, 4: S - s2 - s3}
+
+
+def stratum_search(h, k: int, S: int, ratio3, ratio4, reps: int, seed: int, nulls, exact_profile,
+                   eps: float = EPS) -> np.ndarray:
+    """The appendix's exhaustive search: for every (r3, r4) cell the mean over
+    `reps` estimates (seeds seed, seed + 1, ...) of Pearson's rho between the
+    estimated profile and exact_profile.  Estimates follow Algorithm 4 with the
+    cell's stratum sizes (rounded to float32 as the library returns them)."""
+    nh = h if isinstance(h, Normalised) else normalise(h)
+    n = {j: nh.count(j) for j in range(2, k + 1)}
+    r4s = list(ratio4) if k == 4 else [0.0]
+    out = np.zeros((len(ratio3), len(r4s)))
+    for i, r3 in enumerate(ratio3):
+        for j, r4 in enumerate(r4s):
+            sizes = stratum_sizes(S, r3, r4, k)
+            sizes = {s: (v if n[s] > 0 else 0) for s, v in sizes.items()}
+            acc = 0.0
+            for r in range(reps):
+                samples = {s: philox.stratum_draws(seed + r, s, n[s], sizes[s]) for s in sizes}
+                raw = sampled_raw(nh, k, samples)
+                est = scale_estimate(raw, k, n, sizes).astype(np.float32).astype(np.float64)
+                acc += quality(relative_abundance(est, nulls, eps), exact_profile)[0]
+            out[i, j] = acc / reps
+    return out
+

@@ -72,6 +72,8 @@ SIGNATURES = {
     "hm_sample_sizes_for": (_int, [_int, _vp, _dbl, _int, _vp]),
     "hm_sample_draw": (_int, [_vp, _int, _dbl, _u64, _int, _vp, _vp, _vp, _vp]),
     "count_sampled": (_int, [_vp, _int, _dbl, _u64, _int, _vp, _vp, _vp]),
+    "count_sampled_sizes": (_int, [_vp, _int, _u64, _u64, _u64, _u64, _vp, _vp, _vp]),
+    "hm_stratum_search": (_int, [_vp, _int, _u64, _vp, _int, _vp, _int, _int, _u64, _vp, _int, _vp, _dbl, _vp, _vp]),
     "count_sampled_indices": (_int, [_vp, _int, _vp, _u64, _vp, _u64, _vp, _u64, _vp, _vp, _vp]),
     "count_nulls": (_int, [_vp, _int, _int, _u64, _vp, _vp, _vp, _vp]),
     "count_nulls_model": (_int, [_vp, _int, _int, _int, _int, _u64, _vp, _vp, _vp, _vp]),
@@ -429,6 +431,35 @@ def hm_profile_quality(est, exact, stream=None):
     out = torch.empty(3, dtype=torch.float64, device="cuda")
     _check(lib().hm_profile_quality(_ptr(est), _ptr(exact), est.numel(), _ptr(out), _stream_ptr(stream)))
     return tuple(float(x) for x in out.cpu().tolist())
+
+
+def count_sampled_sizes(H: Graph, k: int, sizes: dict, seed: int, est=None, raw=None, stream=None):
+    """Algorithm 4 with sizes[j] draws from stratum j; (est fp32[C], raw int64[C])."""
+    import torch
+    n = hm_num_classes(k)
+    if est is None:
+        est = torch.empty(n, dtype=torch.float32, device="cuda")
+    if raw is None:
+        raw = torch.empty(n, dtype=torch.int64, device="cuda")
+    _check(lib().count_sampled_sizes(H.handle, k, int(sizes.get(2, 0)), int(sizes.get(3, 0)), int(sizes.get(4, 0)),
+                                     int(seed) & (2**64 - 1), _ptr(est), _ptr(raw), _stream_ptr(stream)))
+    return est, raw
+
+
+def hm_stratum_search(H: Graph, k: int, S: int, ratio3, ratio4, reps: int, seed: int, nulls, exact_profile,
+                      eps: float = 4.0, stream=None) -> np.ndarray:
+    """Mean Pearson correlation per (ratio3[i], ratio4[j]) cell, as a numpy array [n3, n4]."""
+    import torch
+    r3 = np.ascontiguousarray(ratio3, dtype=np.float64)
+    r4 = np.ascontiguousarray(ratio4 if k == 4 else [0.0], dtype=np.float64)
+    nulls = torch.as_tensor(nulls).to(device="cuda", dtype=torch.float64).contiguous()
+    prof = torch.as_tensor(exact_profile).to(device="cuda", dtype=torch.float64).contiguous()
+    rho = np.zeros((len(r3), len(r4)), dtype=np.float64)
+    _check(lib().hm_stratum_search(H.handle, k, int(S), r3.ctypes.data_as(ctypes.c_void_p), len(r3),
+                                   r4.ctypes.data_as(ctypes.c_void_p), len(r4), int(reps), int(seed) & (2**64 - 1),
+                                   _ptr(nulls), nulls.shape[0], _ptr(prof), float(eps),
+                                   rho.ctypes.data_as(ctypes.c_void_p), _stream_ptr(stream)))
+    return rho
 
 
 def hm_null_tile_sizes(H: Graph):

@@ -40,6 +40,8 @@
 namespace hm {
 
 int count_exact_impl(const hm_graph* H, int k, int64_t* counts, hipStream_t st);
+int sampled_with_sizes(const hm_graph* H, int k, const uint64_t S[5], uint64_t seed, float* est, int64_t* raw,
+                       hipStream_t st);
 
 namespace {
 
@@ -204,6 +206,10 @@ __global__ void k_motif_profile(const double* __restrict__ real, const double* _
       const double d = (x - mu) / (x + mu + eps);
       sp[c] = norm > 0.0 ? d / norm : 0.0;
     }
+}
+
+__global__ void k_f32_to_f64(const float* __restrict__ a, int n, double* __restrict__ b) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) b[i] = double(a[i]);
 }
 
 // Pearson's rho, the largest and the mean absolute error between two
@@ -1496,6 +1502,85 @@ int hm_motif_profile(const double* real, const double* nulls, int n_rand, int n_
   hm::k_motif_profile<<<1, 256, 0, static_cast<hipStream_t>(stream)>>>(real, nulls, uint32_t(n_rand), n_classes, eps,
                                                                        delta, sp);
   HM_HIP(hipGetLastError());
+  return HM_OK;
+}
+
+int hm_stratum_search(const hm_graph* H, int k, uint64_t S, const double* ratio3, int n3, const double* ratio4, int n4,
+                      int reps, uint64_t seed, const double* nulls, int n_rand, const double* exact_profile, double eps,
+                      double* rho, void* stream) {
+  if (!H || !ratio3 || !nulls || !exact_profile || !rho || (k == 4 && !ratio4)) {
+    hm::set_error("NULL argument to hm_stratum_search");
+    return HM_EINVAL;
+  }
+  if (k != 3 && k != 4) {
+    hm::set_error("order %d is not supported (3 or 4)", k);
+    return HM_EUNSUPPORTED;
+  }
+  if (k == 3) n4 = 1;
+  if (S == 0 || S >= (1ull << 31) || n3 < 1 || n4 < 1 || uint64_t(n3) * n4 > 4096 || reps < 1 || reps > 1024 ||
+      n_rand < 1 || !(eps >= 0.0)) {
+    hm::set_error("hm_stratum_search: bad sizes (S, grid, reps or n_rand)");
+    return HM_EINVAL;
+  }
+  for (int i = 0; i < n3; ++i)
+    if (!(ratio3[i] >= 0.0)) {
+      hm::set_error("stratum ratios must be >= 0");
+      return HM_EINVAL;
+    }
+  for (int i = 0; k == 4 && i < n4; ++i)
+    if (!(ratio4[i] >= 0.0)) {
+      hm::set_error("stratum ratios must be >= 0");
+      return HM_EINVAL;
+    }
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int C = hm::class_tables().n_classes[k];
+  const uint64_t cells = uint64_t(n3) * n4;
+  std::vector<void*> bufs;
+  struct Free {
+    std::vector<void*>& b;
+    hipStream_t st;
+    ~Free() { hm::dfree_on(b.data(), b.size(), st); }
+  } release{bufs, st};
+  auto get = [&](void** p, size_t bytes) {
+    int rc = hm::dalloc(p, bytes);
+    if (rc == HM_OK) bufs.push_back(*p);
+    return rc;
+  };
+  void *est_p = nullptr, *estd_p = nullptr, *delta_p = nullptr, *q_p = nullptr;
+  HM_TRY(get(&est_p, sizeof(float) * C));
+  HM_TRY(get(&estd_p, sizeof(double) * C));
+  HM_TRY(get(&delta_p, sizeof(double) * C));
+  HM_TRY(get(&q_p, sizeof(double) * 3 * cells * reps));
+  float* est = static_cast<float*>(est_p);
+  double* estd = static_cast<double*>(estd_p);
+  double* delta = static_cast<double*>(delta_p);
+  double* q = static_cast<double*>(q_p);
+  for (int i = 0; i < n3; ++i)
+    for (int j = 0; j < n4; ++j) {
+      // S_2 : S_3 : S_4 = 1 : ratio3 : ratio4 with S_2 + S_3 + S_4 = S
+      const double r3 = ratio3[i], r4 = k == 4 ? ratio4[j] : 0.0;
+      uint64_t Sj[5] = {0, 0, 0, 0, 0};
+      Sj[2] = uint64_t(std::llround(double(S) / (1.0 + r3 + r4)));
+      Sj[3] = std::min<uint64_t>(S - Sj[2], uint64_t(std::llround(r3 * double(Sj[2]))));
+      Sj[4] = k == 4 ? S - Sj[2] - Sj[3] : 0;
+      if (k == 3) Sj[3] = S - Sj[2];
+      for (int r = 0; r < reps; ++r) {
+        const uint64_t cell = uint64_t(i) * n4 + j;
+        HM_TRY(hm::sampled_with_sizes(H, k, Sj, seed + uint64_t(r), est, nullptr, st));
+        hm::k_f32_to_f64<<<1, 256, 0, st>>>(est, C, estd);
+        hm::k_motif_profile<<<1, 256, 0, st>>>(estd, nulls, uint32_t(n_rand), C, eps, delta, nullptr);
+        hm::k_profile_quality<<<1, 256, 0, st>>>(delta, exact_profile, C, q + 3 * (cell * reps + r));
+        HM_HIP(hipGetLastError());
+      }
+    }
+  std::vector<double> host(3 * cells * reps);
+  HM_HIP(hipMemcpyAsync(host.data(), q, sizeof(double) * host.size(), hipMemcpyDeviceToHost, st));
+  HM_HIP(hipStreamSynchronize(st));
+  for (uint64_t c = 0; c < cells; ++c) {
+    double s = 0.0;
+    for (int r = 0; r < reps; ++r) s += host[3 * (c * reps + r)];
+    rho[c] = s / double(reps);
+  }
   return HM_OK;
 }
 

@@ -1276,6 +1276,17 @@ int enumerate_samples(const hm_graph* H, int k, const uint32_t* const idx[5], co
   return launch_sampled(H, k, idx, S, 0, ps, row0, nullptr, nullptr, st);
 }
 
+// Draw S[j] samples of each stratum in the kernel and scale (Algorithm 4 with
+// the stratum sizes given).
+int sampled_with_sizes(const hm_graph* H, int k, const uint64_t S[5], uint64_t seed, float* est, int64_t* raw,
+                       hipStream_t st) {
+  const uint32_t* idx[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  const uint64_t row0[5] = {0, 0, 0, 0, 0};
+  uint64_t s[5] = {0, 0, 0, 0, 0};
+  for (int j = 2; j <= k; ++j) s[j] = H->n_by_size[j] ? S[j] : 0;
+  return launch_sampled(H, k, idx, s, seed, nullptr, row0, est, raw, st);
+}
+
 // Enumerate around explicit samples and scale (Algorithm 4).
 int sampled_from_indices(const hm_graph* H, int k, const uint32_t* const idx[5], const uint64_t S[5], float* est,
                          int64_t* raw, hipStream_t st) {
@@ -1348,6 +1359,25 @@ int count_sampled(const hm_graph* H, int k, double fraction, uint64_t seed, int 
   const uint32_t* idx[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};   // drawn in the kernel
   const uint64_t row0[5] = {0, 0, 0, 0, 0};
   return hm::launch_sampled(H, k, idx, S, seed, nullptr, row0, est, raw, st);
+}
+
+int count_sampled_sizes(const hm_graph* H, int k, uint64_t s2, uint64_t s3, uint64_t s4, uint64_t seed, float* est,
+                        int64_t* raw, void* stream) {
+  if (!H || !est) {
+    hm::set_error("NULL argument to count_sampled_sizes");
+    return HM_EINVAL;
+  }
+  if (k != 3 && k != 4) {
+    hm::set_error("order %d is not supported (3 or 4)", k);
+    return HM_EUNSUPPORTED;
+  }
+  const uint64_t limit = 1ull << 31;
+  if (s2 >= limit || s3 >= limit || s4 >= limit) {
+    hm::set_error("a stratum sample size of 2^31 or more");
+    return HM_EINVAL;
+  }
+  const uint64_t S[5] = {0, 0, s2, s3, k == 4 ? s4 : 0};
+  return hm::sampled_with_sizes(H, k, S, seed, est, raw, static_cast<hipStream_t>(stream));
 }
 
 int count_sampled_indices(const hm_graph* H, int k, const uint32_t* idx2, uint64_t s2, const uint32_t* idx3,

@@ -105,3 +105,49 @@ def test_bad_model_arguments(hm):
             hm.count_nulls_model(g, 4, 4, hm.HM_NULL_CONFIG, 0, 1)
         with pytest.raises(hm.HMError):
             hm.hm_null_export_model(g, hm.HM_NULL_CONFIG, 5000, 1, 0)
+
+
+def test_sampled_sizes_match_oracle(hm):
+    """count_sampled_sizes: explicit draws per stratum, raw counts bit-exact."""
+    from oracle import philox
+    h = W.random_small(9300, 40, 300, {2: 0.5, 3: 0.3, 4: 0.2})
+    nh = core.normalise(h)
+    n = {j: nh.count(j) for j in (2, 3, 4)}
+    for sizes in ({2: 7, 3: 0, 4: 13}, {2: 1, 3: 50, 4: 2}, {2: 0, 3: 0, 4: 5}):
+        with hm.hm_graph_create(h.members, h.offsets, h.n_nodes) as g:
+            est, raw = hm.count_sampled_sizes(g, 4, sizes, 123)
+        samples = {j: philox.stratum_draws(123, j, n[j], sizes[j]) for j in sizes}
+        want_raw = core.sampled_raw(nh, 4, samples)
+        assert np.array_equal(raw.cpu().numpy(), want_raw), sizes
+        want_est = core.scale_estimate(want_raw, 4, n, sizes).astype(np.float32)
+        assert np.array_equal(est.cpu().numpy(), want_est), sizes
+
+
+def test_stratum_search_matches_oracle(hm):
+    """The appendix's grid search over S_3 / S_2 and S_4 / S_2: the mean
+    correlation of every cell equals the oracle's (the same draws, the same
+    float32 estimates; fp64 profiles and correlations)."""
+    h = W.random_small(9400, 35, 260, {2: 0.55, 3: 0.3, 4: 0.15})
+    k, R, S, reps, seed = 4, 6, 90, 3, 40
+    with hm.hm_graph_create(h.members, h.offsets, h.n_nodes) as g:
+        real, nl, _ = hm.count_nulls_model(g, k, R, hm.HM_NULL_CONFIG, 3, 2)
+        delta, _ = hm.hm_motif_profile(real.double(), nl.double())
+        r3, r4 = [0.5, 1.0, 3.0], [1.0, 2.0]
+        got = hm.hm_stratum_search(g, k, S, r3, r4, reps, seed, nl.double(), delta)
+        with pytest.raises(hm.HMError):
+            hm.hm_stratum_search(g, k, 0, r3, r4, reps, seed, nl.double(), delta)
+        with pytest.raises(hm.HMError):
+            hm.hm_stratum_search(g, k, S, [-1.0], r4, reps, seed, nl.double(), delta)
+    nulls_np = nl.cpu().numpy()
+    prof = profiles.relative_abundance(real.cpu().numpy(), nulls_np)
+    want = profiles.stratum_search(h, k, S, r3, r4, reps, seed, nulls_np, prof)
+    np.testing.assert_allclose(got, want, rtol=1e-11, atol=1e-12)
+    # order 3: one column
+    with hm.hm_graph_create(h.members, h.offsets, h.n_nodes) as g:
+        real3, nl3, _ = hm.count_nulls_model(g, 3, R, hm.HM_NULL_CONFIG, 3, 2)
+        d3, _ = hm.hm_motif_profile(real3.double(), nl3.double())
+        got3 = hm.hm_stratum_search(g, 3, 40, [0.5, 2.0], None, 2, seed, nl3.double(), d3)
+    n3 = nl3.cpu().numpy()
+    want3 = profiles.stratum_search(h, 3, 40, [0.5, 2.0], None, 2, seed, n3,
+                                    profiles.relative_abundance(real3.cpu().numpy(), n3))
+    np.testing.assert_allclose(got3, want3, rtol=1e-11, atol=1e-12)

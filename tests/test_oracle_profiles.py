@@ -88,3 +88,26 @@ def test_quality_measures():
     assert np.isclose(mx, 0.2) and np.isclose(mae, 0.35 / 5)
     # Pearson's rho by its definition on a hand case: x = (1, 2, 3), y = (1, 3, 2)
     assert np.isclose(profiles.quality([1, 2, 3], [1, 3, 2])[0], 0.5)
+
+
+def test_stratum_sizes_rule():
+    """S = 60 split 1 : 3 : 2 gives 10 / 30 / 20; rounding and the k = 3 form."""
+    assert profiles.stratum_sizes(60, 3, 2) == {2: 10, 3: 30, 4: 20}
+    assert profiles.stratum_sizes(10, 1, 1) == {2: 3, 3: 3, 4: 4}          # 10/3 = 3.33 -> 3
+    assert profiles.stratum_sizes(7, 0.5, 0.0) == {2: 5, 3: 2, 4: 0}       # 7/1.5 = 4.67 -> 5; 2.5 -> 3, capped at 2
+    assert profiles.stratum_sizes(9, 2, 0, k=3) == {2: 3, 3: 6}
+
+
+def test_stratum_search_consistency():
+    """Algorithm 4 is consistent: with many draws in every cell the
+    estimated profiles approach the exact one and every cell's mean
+    correlation approaches 1; with few draws it is lower somewhere."""
+    h = W.random_small(710, 30, 200, {2: 0.6, 3: 0.3, 4: 0.1})
+    exact = core.count_exact(h, 4)
+    null = np.array([core.count_exact(W.Hypergraph(h.n_nodes, *profiles.config_model(h, 3, 1, c)), 4)
+                     for c in range(4)])
+    prof = profiles.relative_abundance(exact, null)
+    big = profiles.stratum_search(h, 4, 6000, [1.0, 3.0], [1.0, 2.0], 2, 5, null, prof)
+    small = profiles.stratum_search(h, 4, 40, [1.0, 3.0], [1.0, 2.0], 2, 5, null, prof)
+    assert big.shape == (2, 2) and np.all(big > 0.97) and np.all(big <= 1 + 1e-12)
+    assert small.min() < big.min()
