@@ -66,7 +66,16 @@ def _unit_counts(e2: np.ndarray, e3: np.ndarray, n_nodes: int, words: int) -> di
         t = e3.astype(np.int64)
         cand = int(deg2[t[:, 0]].sum() + deg2[t[:, 1]].sum() + deg2[t[:, 2]].sum()
                    + deg3[t[:, 0]].sum() + deg3[t[:, 1]].sum())
-    return {"c4_word_tasks": int(ys) * words, "b4_word_tasks": int(len(e3)) * words, "b4_candidates": cand}
+    # case (c) by graph identities: per pair of G2 its W common-neighbour words
+    # and, per common neighbour above the pair, W words of edges among them;
+    # per node pair u < w its W codegree words
+    above = 0
+    for r, x in e2.tolist():
+        i = np.searchsorted(rows[r], x, side="right")
+        above += len(np.intersect1d(rows[r][i:], rows[x], assume_unique=True))
+    return {"c4_word_tasks": int(ys) * words, "b4_word_tasks": int(len(e3)) * words, "b4_candidates": cand,
+            "id_edge_word_tasks": int(len(e2)) * words, "id_k4_word_tasks": int(above) * words,
+            "id_c4_pair_word_tasks": n * (n - 1) // 2 * words}
 
 
 def _b4_lookup_model(e2: np.ndarray, e3: np.ndarray, e4: np.ndarray, n_nodes: int,
@@ -484,6 +493,48 @@ def main() -> int:
     ok = [k for k, v in sampled.items() if v["mre"] <= 0.02]
     best = min(ok, key=lambda k: float(k)) if ok else None
 
+    # Section 6.3 and Table 3: motif profiles against 10 configuration-model
+    # draws (counted exactly), and the accuracy of profiles whose observed
+    # counts are sampled (rho, MaxAE, MAE, mean over 10 repetitions); then the
+    # appendix's stratum-budget search (Fig. 6) at 1% of the hyperedges
+    profile_acc = None
+    if not args.exact_only:
+        sweeps = 10
+        t0 = time.perf_counter()
+        real_c, null_c, _ = hm.count_nulls_model(g, 4, 10, hm.HM_NULL_CONFIG, sweeps, 1, stream=stream)
+        torch.cuda.synchronize()
+        null_ms = (time.perf_counter() - t0) * 1e3
+        t0 = time.perf_counter()
+        hm.count_nulls_model(g, 4, 10, hm.HM_NULL_CONFIG, sweeps, 2, stream=stream)
+        torch.cuda.synchronize()
+        null_ms_replay = (time.perf_counter() - t0) * 1e3
+        nd = null_c.double()
+        exact_prof, _ = hm.hm_motif_profile(real_c.double(), nd)
+        acc = {}
+        for f in (0.01, 0.02, 0.05, 0.10):
+            qs = []
+            for rep in range(10):
+                est, _ = hm.count_sampled(g, 4, f, 5000 + rep, stream=stream)
+                d, _ = hm.hm_motif_profile(est.double(), nd)
+                qs.append(hm.hm_profile_quality(d, exact_prof))
+            q = np.array(qs)
+            acc[f"{f:g}"] = {"rho": float(q[:, 0].mean()), "max_ae": float(q[:, 1].mean()),
+                             "mae": float(q[:, 2].mean())}
+        S = int(0.01 * (stats["n2"] + stats["n3"] + stats["n4"]))
+        r3, r4 = [1.0, 2.0, 3.0, 4.0, 5.0], [1.0, 2.0, 3.0, 4.0]
+        t0 = time.perf_counter()
+        rho = hm.hm_stratum_search(g, 4, S, r3, r4, 10, 7000, nd, exact_prof, stream=stream)
+        search_ms = (time.perf_counter() - t0) * 1e3
+        bi, bj = np.unravel_index(int(np.argmax(rho)), rho.shape)
+        profile_acc = {"null": "configuration model, 10 draws, 10 reshuffle sweeps",
+                       "null_first_call_ms": null_ms, "null_ms_per_batch": null_ms_replay,
+                       "sampled_profile_accuracy": acc,
+                       "stratum_search": {"S": S, "ratio3": r3, "ratio4": r4, "reps": 10, "ms": search_ms,
+                                          "mean_rho": rho.tolist(),
+                                          "best": {"S3_over_S2": r3[bi], "S4_over_S2": r4[bj],
+                                                   "rho": float(rho[bi, bj])},
+                                          "paper_split_1_3_2_rho": float(rho[2, 1])}}
+
     # batched null model: 64 stub-matched copies counted at k = 4 in one graph launch
     nulls = None
     if not args.exact_only:
@@ -508,10 +559,13 @@ def main() -> int:
     avg_s = kernels[dom]["avg_ms"] / 1e3
     if dom == "k_exact4_bits":
         # the fused counting launch; its work is integer logic on adjacency words
-        # held in cache: per (pair, y, word) task of case (c) 7 popcounts and
-        # about 17 further logic/add operations, per (3-node hyperedge, word) of
-        # case (b) 7 popcounts and about 21 further operations
-        ops = units["c4_word_tasks"] * 24 + units["b4_word_tasks"] * 28
+        # held in LDS.  Case (c) by graph identities: per (pair, word) an AND, a
+        # mask, a popcount and an add (4); per (pair, common neighbour, word) of
+        # the 4-clique count the same 4; per (node pair, word) of the codegrees
+        # an AND, a popcount and an add (3).  Case (b): per (3-node hyperedge,
+        # word) 7 popcounts and about 21 further operations (28)
+        ops = (units["id_edge_word_tasks"] * 4 + units["id_k4_word_tasks"] * 4
+               + units["id_c4_pair_word_tasks"] * 3 + units["b4_word_tasks"] * 28)
         roof = {"bound": "alu", "achieved": ops / avg_s / 1e12, "peak": ALU_PEAK_TOPS, "unit": "Tops/s",
                 "frac": ops / avg_s / 1e12 / ALU_PEAK_TOPS, "traffic": traffic.get(dom)}
     else:
@@ -563,6 +617,7 @@ def main() -> int:
         "sampled_speedup_at_2pct": ({"fraction": float(best), "speedup": sampled[best]["speedup_vs_exact_count"]}
                                     if best else None),
         "nulls": nulls,
+        "profiles": profile_acc,
         "large_workloads": large,
         "kernels": kernels,
         "units": units,

@@ -62,10 +62,18 @@ struct ClassMask {
   unsigned long long w[4];
 };
 
+// Classes of the six connected 4-node graphs; with `on`, their G2 counts come
+// from the seven identity sums at kIdAcc rather than from the G2 region.
+struct IdShapes {
+  int on;
+  int path, star, cycle, paw, diamond, clique;
+};
+
 // (one workgroup of 256 threads; sums the kHistCopies copies of hist and
 // leaves them zero)
 __global__ void k_combine(unsigned long long* __restrict__ hist, int n_classes, ClassMask pairs_only,
-                          int64_t* __restrict__ counts) {
+                          int64_t* __restrict__ counts, IdShapes sh) {
+  __shared__ unsigned long long ids[8];
   const int c = threadIdx.x;
   unsigned long long m = 0, s = 0, g = 0;
   for (uint32_t q = 0; q < kHistCopies; ++q) {
@@ -76,6 +84,28 @@ __global__ void k_combine(unsigned long long* __restrict__ hist, int n_classes, 
     h[kMain + c] = 0;
     h[kSub + c] = 0;
     h[kG2 + c] = 0;
+  }
+  if (sh.on) {
+    if (c < 7) {
+      unsigned long long a = 0;
+      for (uint32_t q = 0; q < kHistCopies; ++q) {
+        unsigned long long* h = hist + uint64_t(q) * kExactHistStride + kIdAcc;
+        a += h[c];
+        h[c] = 0;
+      }
+      ids[c] = a;
+    }
+    __syncthreads();
+    // induced counts from the non-induced ones (each shape's copies inside
+    // the larger shapes subtracted, largest first)
+    const unsigned long long T = ids[0] / 3, k4 = ids[4];
+    const unsigned long long dia = ids[2] - 6 * k4;
+    const unsigned long long cyc = ids[5] / 2 - dia - 3 * k4;
+    const unsigned long long paw = ids[3] / 2 - 4 * dia - 12 * k4;
+    const unsigned long long star = ids[6] - paw - 2 * dia - 4 * k4;
+    const unsigned long long path = (ids[1] - 3 * T) - 4 * cyc - 2 * paw - 6 * dia - 12 * k4;
+    g = c == sh.clique ? k4 : c == sh.diamond ? dia : c == sh.cycle ? cyc : c == sh.paw ? paw
+        : c == sh.star ? star : c == sh.path ? path : 0ull;
   }
   if (c < n_classes) {
     unsigned long long v = m;
@@ -114,10 +144,10 @@ struct ExactArgs {
 // with LB, a copy of the whole bit matrix (N x W words) and of the row
 // starts of G2 and of the incidence lists, so that every adjacency word and
 // row bound the items read comes from LDS rather than from L2.
-template <bool LB>
+template <bool LB, bool ID>
 __global__ void __launch_bounds__(kExact4Threads) k_exact4_bits(ExactArgs a) {
   __shared__ uint8_t lut[2048];
-  __shared__ unsigned long long h_main[256], h_sub[256], h_g2[256];
+  __shared__ unsigned long long h_main[256], h_sub[256], h_g2[256], h_id[8];
   __shared__ uint32_t ylist[kExact4Waves][kWave];
   extern __shared__ uint32_t dyn_lds[];
   View v = a.v;
@@ -148,21 +178,28 @@ __global__ void __launch_bounds__(kExact4Threads) k_exact4_bits(ExactArgs a) {
     h_sub[threadIdx.x] = 0;
     h_g2[threadIdx.x] = 0;
   }
+  if (threadIdx.x < 8) h_id[threadIdx.x] = 0;
   __syncthreads();
   const int wv = threadIdx.x / kWave;
   const uint32_t lane = threadIdx.x & (kWave - 1);
   uint32_t* sets = b4_sets + wv * b4_set_words(v.W);
   const C4Lanes L = c4_lanes(v.W);
   C4Acc acc;
-  c4_zero(acc);
-  const uint64_t n23 = a.n2 + a.n3;
+  IdAcc ida;
+  if (ID) id_zero(ida); else c4_zero(acc);
+  // (c) items: the pairs of G2, then (identity route) one per node
+  const uint64_t nc = ID ? a.n2 + v.N : a.n2;
+  const uint64_t n23 = nc + a.n3;
   const uint64_t items = n23 + (a.n4 + kA4Chunk - 1) / kA4Chunk;
   const uint64_t n_waves = uint64_t(gridDim.x) * kExact4Waves;
   for (uint64_t i = uint64_t(blockIdx.x) * kExact4Waves + wv; i < items; i += n_waves) {
     if (i < a.n2) {
-      c4_bits_item(v, v.e2[2 * i], v.e2[2 * i + 1], L, ylist[wv], acc, lut, h_g2);
+      if (ID) id_edge_item(v, v.e2[2 * i], v.e2[2 * i + 1], L, ylist[wv], ida);
+      else c4_bits_item(v, v.e2[2 * i], v.e2[2 * i + 1], L, ylist[wv], acc, lut, h_g2);
+    } else if (i < nc) {
+      id_node_item(v, uint32_t(i - a.n2), ida);
     } else if (i < n23) {
-      b4_item(v, i - a.n2, sets, lut, h_main, h_sub);
+      b4_item(v, i - nc, sets, lut, h_main, h_sub);
     } else {
       const uint64_t e = (i - n23) * kA4Chunk + lane;
       if (e < a.n4)
@@ -170,12 +207,12 @@ __global__ void __launch_bounds__(kExact4Threads) k_exact4_bits(ExactArgs a) {
                     kPairBits4);
     }
   }
-  c4_flush(acc, lut, h_g2);
+  if (ID) id_flush(ida, h_id); else c4_flush(acc, lut, h_g2);
   __syncthreads();
   unsigned long long* hc = hist_copy(a.hist, kExactHistStride);
   flush(h_main, hc + kMain, 256);
   flush(h_sub, hc + kSub, 256);
-  flush(h_g2, hc + kG2, 256);
+  if (ID) flush(h_id, hc + kIdAcc, 8); else flush(h_g2, hc + kG2, 256);
 }
 
 // Order 3: thread items [0, n2 * W) are the (pair, word) tasks of case (c),
@@ -253,9 +290,31 @@ unsigned grid_threads(uint64_t items, unsigned cap = kCountGrid, unsigned per_bl
   return unsigned(g);
 }
 
+// Largest node count for which the identity route counts case (c): its node
+// items take every node pair once (N^2 W / 2 word operations).
+constexpr uint64_t kIdPairWordsMax = 1ull << 28;
+
+bool use_identities(const View& v) { return uint64_t(v.N) * v.N * v.W / 2 <= kIdPairWordsMax; }
+
+// Shape classes for k_combine (on: the identity route counted case (c)).
+IdShapes id_shapes(bool on) {
+  const ClassTables& t = class_tables();
+  IdShapes sh;
+  sh.on = on ? 1 : 0;
+  // representative pair patterns (local nodes 0..3; bits: 01=0, 02=1, 12=2, 03=4, 13=5, 23=7)
+  sh.path = t.lut4[(1u << 0) | (1u << 2) | (1u << 7)];
+  sh.star = t.lut4[(1u << 0) | (1u << 1) | (1u << 4)];
+  sh.cycle = t.lut4[(1u << 0) | (1u << 2) | (1u << 7) | (1u << 4)];
+  sh.paw = t.lut4[(1u << 0) | (1u << 1) | (1u << 2) | (1u << 4)];
+  sh.diamond = t.lut4[(1u << 0) | (1u << 1) | (1u << 2) | (1u << 4) | (1u << 5)];
+  sh.clique = t.lut4[kPairBits4];
+  return sh;
+}
+
 // The fused counting launch of a graph with adjacency bit rows, adding to the
-// kHistCopies counter copies at hist (main, sub and G2 regions).
-void launch_bits_count(const hm_graph* H, int k, const uint8_t* lut, unsigned long long* hist, hipStream_t st) {
+// kHistCopies counter copies at hist (main, sub and G2 regions, or the
+// identity sums).  Returns whether the identity route ran (order 4).
+bool launch_bits_count(const hm_graph* H, int k, const uint8_t* lut, unsigned long long* hist, hipStream_t st) {
   const View v = view_of(H);
   const uint64_t n2 = H->n_by_size[2], n3 = H->n_by_size[3], n4 = H->n_by_size[4];
   ExactArgs a{};
@@ -268,21 +327,29 @@ void launch_bits_count(const hm_graph* H, int k, const uint8_t* lut, unsigned lo
   if (k == 4) {
     const size_t rows = (size_t(v.N) * v.W + 3 * (size_t(v.N) + 1)) * 4;
     const bool lb = rows <= kLdsBitsMaxBytes;
+    const bool id = use_identities(v);
     const size_t lds = size_t(kExact4Waves) * b4_set_words(v.W) * 4 + (lb ? rows : 0);
-    const uint64_t items = n2 + n3 + (n4 + kA4Chunk - 1) / kA4Chunk;
-    const void* kern = lb ? reinterpret_cast<const void*>(k_exact4_bits<true>)
-                          : reinterpret_cast<const void*>(k_exact4_bits<false>);
+    const uint64_t items = n2 + (id ? v.N : 0) + n3 + (n4 + kA4Chunk - 1) / kA4Chunk;
+    const void* kern = lb ? (id ? reinterpret_cast<const void*>(k_exact4_bits<true, true>)
+                                : reinterpret_cast<const void*>(k_exact4_bits<true, false>))
+                          : (id ? reinterpret_cast<const void*>(k_exact4_bits<false, true>)
+                                : reinterpret_cast<const void*>(k_exact4_bits<false, false>));
     const unsigned grid = fused_grid(kern, lds, items, kExact4Waves, kExact4Threads);
     ProfileScope ps("k_exact4_bits", st);
-    if (lb)
-      k_exact4_bits<true><<<grid, kExact4Threads, lds, st>>>(a);
+    if (lb && id)
+      k_exact4_bits<true, true><<<grid, kExact4Threads, lds, st>>>(a);
+    else if (lb)
+      k_exact4_bits<true, false><<<grid, kExact4Threads, lds, st>>>(a);
+    else if (id)
+      k_exact4_bits<false, true><<<grid, kExact4Threads, lds, st>>>(a);
     else
-      k_exact4_bits<false><<<grid, kExact4Threads, lds, st>>>(a);
-  } else {
-    const unsigned grid = fused_grid(reinterpret_cast<const void*>(k_exact3_bits), 0, n2 * v.W + n3, kThreads);
-    ProfileScope ps("k_exact3_bits", st);
-    k_exact3_bits<<<grid, kThreads, 0, st>>>(a);
+      k_exact4_bits<false, false><<<grid, kExact4Threads, lds, st>>>(a);
+    return id;
   }
+  const unsigned grid = fused_grid(reinterpret_cast<const void*>(k_exact3_bits), 0, n2 * v.W + n3, kThreads);
+  ProfileScope ps("k_exact3_bits", st);
+  k_exact3_bits<<<grid, kThreads, 0, st>>>(a);
+  return false;
 }
 
 ClassMask pairs_only_mask(int k) {
@@ -361,8 +428,9 @@ int count_exact_impl(const hm_graph* H, int k, int64_t* counts, hipStream_t st) 
   } guard{H};
   const uint64_t n3 = H->n_by_size[3], n4 = H->n_by_size[4];
   const View v = view_of(H);
+  bool id = false;
   if (v.bits) {
-    launch_bits_count(H, k, k == 4 ? lut4 : lut3, H->hist, st);
+    id = launch_bits_count(H, k, k == 4 ? lut4 : lut3, H->hist, st);
   } else {
     if (k == 4 && n4) {
       ProfileScope ps("k_case_a4", st);
@@ -376,7 +444,7 @@ int count_exact_impl(const hm_graph* H, int k, int64_t* counts, hipStream_t st) 
     HM_TRY(count_sparse(H, k, st));
   }
   HM_HIP(hipGetLastError());
-  k_combine<<<1, 256, 0, st>>>(H->hist, t.n_classes[k], pairs_only, counts);
+  k_combine<<<1, 256, 0, st>>>(H->hist, t.n_classes[k], pairs_only, counts, id_shapes(id));
   HM_HIP(hipGetLastError());
   guard.ok = true;
   return HM_OK;
@@ -428,9 +496,9 @@ extern "C" int count_exact_noalloc(const hm_graph* H, int k, int64_t* counts, vo
   hm::k_noalloc_prepare<<<16, 256, 0, st>>>(s, luts);
   HM_HIP(hipGetLastError());
   const uint8_t* lut = reinterpret_cast<const uint8_t*>(s + hm::kNoAllocHistWords) + (k == 4 ? 0 : 2048);
-  hm::launch_bits_count(H, k, lut, s, st);
+  const bool id = hm::launch_bits_count(H, k, lut, s, st);
   HM_HIP(hipGetLastError());
-  hm::k_combine<<<1, 256, 0, st>>>(s, t.n_classes[k], hm::pairs_only_mask(k), counts);
+  hm::k_combine<<<1, 256, 0, st>>>(s, t.n_classes[k], hm::pairs_only_mask(k), counts, hm::id_shapes(id));
   HM_HIP(hipGetLastError());
   return HM_OK;
 }

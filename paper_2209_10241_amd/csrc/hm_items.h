@@ -63,6 +63,7 @@ constexpr int kMain = 0;    // classes counted by (a) and (b)
 constexpr int kSub = 256;   // G2 shape of G2-connected sets counted by (a) and (b)
 constexpr int kG2 = 512;    // G2 shape counts of all connected sets of G2
 constexpr int kHistWords = 768;
+constexpr int kIdAcc = 768;  // the seven sums of the identity route for (c) (exact counts only)
 
 // (a) at order 4: the pattern of a 4-node hyperedge; local positions a..d = 0..3
 __device__ inline uint32_t a4_pattern(const View& v, uint32_t a, uint32_t b, uint32_t c, uint32_t d) {
@@ -288,6 +289,130 @@ __device__ inline void c4_flush(const C4Acc& a, const uint8_t* lut, unsigned lon
   c4_emit(a.paw, rx | xy | xz | yz, lut, h_g2);
   c4_emit(a.star, rx | xy | xz, lut, h_g2);
   c4_emit(a.path, rx | xy | yz, lut, h_g2);
+}
+
+// ---------------------------------------------------------------- (c), order 4, by graph identities
+// The induced pairwise shapes of G2's connected 4-node sets follow from seven
+// sums over G2 (each a count of non-induced copies of a small graph):
+//   t3   = sum over edges of t_e (|N(u) n N(v)|; = 3 x triangles)
+//   p4   = sum over edges of (d_u - 1)(d_v - 1)   (3-paths, plus 3 x triangles)
+//   dia  = sum over edges of C(t_e, 2)           (diamonds through their diagonal)
+//   paw2 = sum over edges of t_e (d_u + d_v - 4) (= 2 x sum over nodes t_v (d_v - 2))
+//   k4   = 4-cliques, each from its smallest edge {u < v}: pairs w < x of
+//          common neighbours above v with w ~ x
+//   c4x2 = sum over node pairs u < w of C(|N(u) n N(w)|, 2) (= 2 x 4-cycles)
+//   star = sum over nodes of C(d, 3)
+// and k_combine turns them into induced counts by inverting the containment
+// of each shape in the larger ones.  Edge items (one per edge of G2) and node
+// items (one per node) run on bit rows.
+struct IdAcc {
+  unsigned long long t3, p4, dia, paw2, k4, c4x2, star;
+};
+
+__device__ inline void id_zero(IdAcc& a) { a.t3 = a.p4 = a.dia = a.paw2 = a.k4 = a.c4x2 = a.star = 0; }
+
+// degree of node x from the row starts
+__device__ inline uint32_t g2_degree(const View& v, uint32_t x) { return v.g2_off[x + 1] - v.g2_off[x]; }
+
+// Edges among the listed common neighbours ys[0..cnt) of {u, x} (all above
+// x): lane (g, word) of C4Lanes takes the w of its group and adds the
+// popcount of C'[word] & N(w)[word] above w.
+__device__ inline void id_k4_list(const View& v, const uint32_t* Ru, const uint32_t* Rx, uint32_t x, const C4Lanes& L,
+                                  const uint32_t* ys, uint32_t cnt, IdAcc& acc) {
+  if (!L.on) return;
+  const uint32_t W = v.W;
+  for (uint32_t ww = L.w0; ww < W; ww += L.wstep) {
+    const uint32_t cw = Ru[ww] & Rx[ww] & mask_gt(x, ww);
+    if (!cw) continue;
+    uint32_t k = 0;
+    for (uint32_t j = L.g; j < cnt; j += L.G) {
+      const uint32_t y = ys[j];
+      k += __popc(cw & v.bits[uint64_t(y) * W + ww] & mask_gt(y, ww));
+    }
+    acc.k4 += k;
+  }
+}
+
+// One wavefront per edge {u < x}; ys: 64 words of wavefront-private LDS.
+// The common neighbours above x, C', are listed in ys (each lane writing the
+// set bits of its word at its offset in a wavefront scan) when they number
+// at most 64, else taken one set bit per lane per round.
+__device__ inline void id_edge_item(const View& v, uint32_t u, uint32_t x, const C4Lanes& L, uint32_t* ys,
+                                    IdAcc& acc) {
+  const uint32_t lane = threadIdx.x & (kWave - 1);
+  const uint32_t W = v.W;
+  const uint32_t* Ru = v.bits + uint64_t(u) * W;
+  const uint32_t* Rx = v.bits + uint64_t(x) * W;
+  uint32_t t_lane = 0, c_word = 0;
+  for (uint32_t w = lane; w < W; w += kWave) {
+    const uint32_t cn = Ru[w] & Rx[w];
+    t_lane += __popc(cn);
+    if (w < uint32_t(kWave)) c_word = cn & mask_gt(x, w);
+  }
+  const uint32_t t = wave_sum_u32(t_lane);
+  if (lane == 0) {
+    const unsigned long long du = g2_degree(v, u), dx = g2_degree(v, x), tt = t;
+    acc.t3 += tt;
+    acc.p4 += (du - 1) * (dx - 1);
+    acc.dia += tt * (tt - 1) / 2;
+    if (tt) acc.paw2 += tt * (du + dx - 4);   // then du, dx >= t + 1 >= 2
+  }
+  if (t < 2) return;   // a 4-clique on {u, x} needs two common neighbours
+  if (W <= uint32_t(kWave)) {
+    uint32_t total;
+    uint32_t off = wave_exclusive_scan(__popc(c_word), &total);
+    if (total <= uint32_t(kWave)) {
+      for (uint32_t b = c_word; b; b &= b - 1) ys[off++] = (lane << 5) | uint32_t(__ffs(b) - 1);
+      wave_sync();
+      id_k4_list(v, Ru, Rx, x, L, ys, total, acc);
+      wave_sync();
+      return;
+    }
+  }
+  for (uint32_t w0 = 0; w0 < W; w0 += kWave) {
+    const uint32_t w = w0 + lane;
+    uint32_t word = w < W ? (Ru[w] & Rx[w] & mask_gt(x, w)) : 0u;
+    while (__ballot(word != 0)) {
+      const bool has = word != 0;
+      const unsigned long long m = __ballot(has);
+      if (has) {
+        ys[__popcll(m & ((1ull << lane) - 1ull))] = (w << 5) | uint32_t(__ffs(word) - 1);
+        word &= word - 1;
+      }
+      wave_sync();
+      id_k4_list(v, Ru, Rx, x, L, ys, uint32_t(__popcll(m)), acc);
+      wave_sync();
+    }
+  }
+}
+
+// One wavefront per node u: C(d_u, 3), and C(|N(u) n N(w)|, 2) for every
+// w > u, one w per lane.
+__device__ inline void id_node_item(const View& v, uint32_t u, IdAcc& acc) {
+  const uint32_t lane = threadIdx.x & (kWave - 1);
+  const uint32_t W = v.W;
+  if (lane == 0) {
+    const unsigned long long d = g2_degree(v, u);
+    acc.star += d < 3 ? 0ull : d * (d - 1) * (d - 2) / 6;
+  }
+  if (g2_degree(v, u) < 2) return;   // no pair of neighbours, no C(c, 2)
+  const uint32_t* Ru = v.bits + uint64_t(u) * W;
+  for (uint32_t w = u + 1 + lane; w < v.N; w += kWave) {
+    const uint32_t* Rw = v.bits + uint64_t(w) * W;
+    uint32_t c = 0;
+    for (uint32_t j = 0; j < W; ++j) c += __popc(Ru[j] & Rw[j]);
+    acc.c4x2 += c < 2 ? 0ull : (unsigned long long)c * (c - 1) / 2;
+  }
+}
+
+// Reduce the sums over the wavefront and add them to the seven counters at
+// h_acc (LDS); every lane of the wavefront must call this.
+__device__ inline void id_flush(const IdAcc& a, unsigned long long* h_acc) {
+  const unsigned long long s[7] = {wave_sum(a.t3), wave_sum(a.p4),   wave_sum(a.dia), wave_sum(a.paw2),
+                                   wave_sum(a.k4), wave_sum(a.c4x2), wave_sum(a.star)};
+  if ((threadIdx.x & (kWave - 1)) == 0)
+    for (int i = 0; i < 7; ++i)
+      if (s[i]) atomicAdd(&h_acc[i], s[i]);
 }
 
 // ---------------------------------------------------------------- (c), order 4, hash set
