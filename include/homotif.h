@@ -203,6 +203,46 @@ int hm_sample_sizes_for(int k, const uint64_t* n_by_size, double fraction, int a
 int count_sampled_sizes(const hm_graph* H, int k, uint64_t s2, uint64_t s3, uint64_t s4, uint64_t seed, float* est,
                         int64_t* raw, void* stream);
 
+/* ---------------------------------------------------------------- order 5 */
+
+/* Section 6.4 samples motifs of order 5, where exact counting does not
+ * reach.  Algorithm 4 at order 5: S_j = ceil(fraction * |E_j|) draws from
+ * the unique hyperedges of each size j = 2..5 (with replacement; draw i of
+ * stratum j is hi64(w * |E_j|), w the first word of Philox4x64-10 at counter
+ * (i, 0, 0, 0) under key (seed, (1 << 32) | j)); each drawn e of size j
+ * counts every 5-node set V containing e whose induced sub-hypergraph is
+ * connected and holds no hyperedge larger than |e|.
+ * A class is reported by its canonical pattern: local positions 0..4 follow
+ * ascending node id, pattern bit b is the b-th subset of {0..4} with at
+ * least two members in ascending subset-mask order (26 bits), and the
+ * canonical pattern is the smallest value over the 120 relabellings.  Its
+ * maxcard j is its largest hyperedge size and countmax the number of its
+ * hyperedges of that size; est = raw * |E_j| / (S_j * countmax), formed in
+ * fp64 and rounded once to fp32 (0 when S_j = 0).
+ * Outputs (device, `capacity` entries): canon (uint32), raw (int64), est
+ * (float), the classes found in ascending canonical order; *n_classes (host)
+ * receives their number.  Synchronous.  The first call on a graph builds its
+ * list and hash set of 5-node hyperedges (kept with the graph).
+ * Limits: each sampled hyperedge may have at most 4096 nodes within
+ * 5 - |e| hops and fewer than 2^32 candidate sets (HM_EUNSUPPORTED past
+ * that: the enumeration is meant for the sparse or small hypergraphs the
+ * paper samples at order 5).
+ * Errors: HM_EINVAL for a NULL argument, a fraction outside (0, 1], or more
+ * classes than capacity (n_classes still tells how many). */
+int count_sampled5(const hm_graph* H, double fraction, uint64_t seed, uint64_t capacity, uint32_t* canon, int64_t* raw,
+                   float* est, uint64_t* n_classes, void* stream);
+
+/* count_sampled5 on explicit draws (device uint32 index arrays per stratum,
+ * with s2..s5 entries; NULL allowed for 0), as count_sampled_indices.
+ * Errors as count_sampled5, and HM_EINVAL for an index outside its stratum. */
+int count_sampled5_indices(const hm_graph* H, const uint32_t* idx2, uint64_t s2, const uint32_t* idx3, uint64_t s3,
+                           const uint32_t* idx4, uint64_t s4, const uint32_t* idx5, uint64_t s5, uint64_t capacity,
+                           uint32_t* canon, int64_t* raw, float* est, uint64_t* n_classes, void* stream);
+
+/* |E_2|, |E_3|, |E_4|, |E_5| (host array of 4): the unique hyperedges of each
+ * size; builds the order-5 structures on first use.  Synchronous. */
+int hm_order5_sizes(const hm_graph* H, uint64_t* n_by_size4, void* stream);
+
 /* Write the drawn stratum indices (device uint32 arrays of S_2, S_3, S_4
  * values; pointers for empty strata may be NULL).  Draw i of stratum j is
  * hi64(w * |E_j|) with w the first word of Philox4x64-10 (Salmon et al.,

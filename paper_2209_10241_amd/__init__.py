@@ -5,7 +5,7 @@ from .binding import (  # noqa: F401
     HM_OPT_SAMPLE_CHUNK_SCALE, count_nulls, count_sampled, count_sampled_indices,
     hm_null_export, hm_null_tile_sizes,
     HM_NULL_CONFIG, HM_NULL_STUBS, count_nulls_model, hm_motif_profile, hm_null_export_model, hm_profile_quality,
-    count_sampled_sizes, hm_stratum_search,
+    count_sampled_sizes, hm_stratum_search, count_sampled5, count_sampled5_indices, hm_order5_sizes,
     Model, count_sampled_learned, count_sampled_weighted_indices, hm_contrib, hm_features, hm_mlp_forward,
     hm_mlp_grad, hm_model_train, hm_proposal_probs,
     hm_get_option, hm_sample_draw, hm_sample_sizes, hm_sample_sizes_for, hm_set_option,

@@ -72,6 +72,9 @@ SIGNATURES = {
     "hm_sample_sizes_for": (_int, [_int, _vp, _dbl, _int, _vp]),
     "hm_sample_draw": (_int, [_vp, _int, _dbl, _u64, _int, _vp, _vp, _vp, _vp]),
     "count_sampled": (_int, [_vp, _int, _dbl, _u64, _int, _vp, _vp, _vp]),
+    "count_sampled5": (_int, [_vp, _dbl, _u64, _u64, _vp, _vp, _vp, _vp, _vp]),
+    "count_sampled5_indices": (_int, [_vp, _vp, _u64, _vp, _u64, _vp, _u64, _vp, _u64, _u64, _vp, _vp, _vp, _vp, _vp]),
+    "hm_order5_sizes": (_int, [_vp, _vp, _vp]),
     "count_sampled_sizes": (_int, [_vp, _int, _u64, _u64, _u64, _u64, _vp, _vp, _vp]),
     "hm_stratum_search": (_int, [_vp, _int, _u64, _vp, _int, _vp, _int, _int, _u64, _vp, _int, _vp, _dbl, _vp, _vp]),
     "count_sampled_indices": (_int, [_vp, _int, _vp, _u64, _vp, _u64, _vp, _u64, _vp, _vp, _vp]),
@@ -460,6 +463,42 @@ def hm_stratum_search(H: Graph, k: int, S: int, ratio3, ratio4, reps: int, seed:
                                    _ptr(nulls), nulls.shape[0], _ptr(prof), float(eps),
                                    rho.ctypes.data_as(ctypes.c_void_p), _stream_ptr(stream)))
     return rho
+
+
+def hm_order5_sizes(H: Graph, stream=None) -> dict:
+    out = (ctypes.c_uint64 * 4)()
+    _check(lib().hm_order5_sizes(H.handle, out, _stream_ptr(stream)))
+    return {2: int(out[0]), 3: int(out[1]), 4: int(out[2]), 5: int(out[3])}
+
+
+def _order5_out(capacity):
+    import torch
+    return (torch.empty(capacity, dtype=torch.int32, device="cuda"),
+            torch.empty(capacity, dtype=torch.int64, device="cuda"),
+            torch.empty(capacity, dtype=torch.float32, device="cuda"))
+
+
+def count_sampled5(H: Graph, fraction: float, seed: int, capacity: int = 1 << 20, stream=None):
+    """Order-5 Algorithm 4: (canonical uint32 numpy, raw int64 numpy, est float32 numpy), ascending canonical."""
+    canon, raw, est = _order5_out(capacity)
+    n = ctypes.c_uint64(0)
+    _check(lib().count_sampled5(H.handle, float(fraction), int(seed) & (2**64 - 1), capacity, _ptr(canon), _ptr(raw),
+                                _ptr(est), ctypes.byref(n), _stream_ptr(stream)))
+    k = n.value
+    return (canon[:k].cpu().numpy().view(np.uint32), raw[:k].cpu().numpy(), est[:k].cpu().numpy())
+
+
+def count_sampled5_indices(H: Graph, samples: dict, capacity: int = 1 << 20, stream=None):
+    """Order-5 Algorithm 4 on explicit draws {j: indices}, j = 2..5."""
+    import torch
+    idx = {j: torch.as_tensor(np.asarray(samples.get(j, []), dtype=np.int32)).to("cuda") for j in (2, 3, 4, 5)}
+    canon, raw, est = _order5_out(capacity)
+    n = ctypes.c_uint64(0)
+    _check(lib().count_sampled5_indices(H.handle, _ptr(idx[2]), idx[2].numel(), _ptr(idx[3]), idx[3].numel(),
+                                        _ptr(idx[4]), idx[4].numel(), _ptr(idx[5]), idx[5].numel(), capacity,
+                                        _ptr(canon), _ptr(raw), _ptr(est), ctypes.byref(n), _stream_ptr(stream)))
+    k = n.value
+    return (canon[:k].cpu().numpy().view(np.uint32), raw[:k].cpu().numpy(), est[:k].cpu().numpy())
 
 
 def hm_null_tile_sizes(H: Graph):

@@ -297,6 +297,14 @@ struct hm_graph {
   // triangles, 4-cliques and 4-cycles through it; over its common neighbours
   // x: sum of t_{ux}, sum of t_{wx}, sum of deg x
   unsigned long long* es = nullptr;
+  // the unique 5-node hyperedges (ascending tuples, first-occurrence order)
+  // and a hash set of their positions (slot = position + 1, 0 empty; hs5_mask
+  // + 1 slots), built on first use at order 5
+  uint32_t* e5 = nullptr;
+  uint32_t* hs5 = nullptr;
+  unsigned long long hs5_mask = 0;
+  uint64_t n5 = 0;
+  bool order5_built = false;
   // raw counters of the sampled counting calls (kHistCopies copies of 256),
   // then the tail and head of their work queue (the two words after one
   // unused); zero between calls
