@@ -62,13 +62,6 @@ struct ClassMask {
   unsigned long long w[4];
 };
 
-// Classes of the six connected 4-node graphs; with `on`, their G2 counts come
-// from the seven identity sums at kIdAcc rather than from the G2 region.
-struct IdShapes {
-  int on;
-  int path, star, cycle, paw, diamond, clique;
-};
-
 // (one workgroup of 256 threads; sums the kHistCopies copies of hist and
 // leaves them zero)
 __global__ void k_combine(unsigned long long* __restrict__ hist, int n_classes, ClassMask pairs_only,
@@ -96,16 +89,7 @@ __global__ void k_combine(unsigned long long* __restrict__ hist, int n_classes, 
       ids[c] = a;
     }
     __syncthreads();
-    // induced counts from the non-induced ones (each shape's copies inside
-    // the larger shapes subtracted, largest first)
-    const unsigned long long T = ids[0] / 3, k4 = ids[4];
-    const unsigned long long dia = ids[2] - 6 * k4;
-    const unsigned long long cyc = ids[5] / 2 - dia - 3 * k4;
-    const unsigned long long paw = ids[3] / 2 - 4 * dia - 12 * k4;
-    const unsigned long long star = ids[6] - paw - 2 * dia - 4 * k4;
-    const unsigned long long path = (ids[1] - 3 * T) - 4 * cyc - 2 * paw - 6 * dia - 12 * k4;
-    g = c == sh.clique ? k4 : c == sh.diamond ? dia : c == sh.cycle ? cyc : c == sh.paw ? paw
-        : c == sh.star ? star : c == sh.path ? path : 0ull;
+    g = id_shape_count(ids, sh, c);
   }
   if (c < n_classes) {
     unsigned long long v = m;
@@ -290,13 +274,9 @@ unsigned grid_threads(uint64_t items, unsigned cap = kCountGrid, unsigned per_bl
   return unsigned(g);
 }
 
-// Largest node count for which the identity route counts case (c): its node
-// items take every node pair once (N^2 W / 2 word operations).
-constexpr uint64_t kIdPairWordsMax = 1ull << 28;
+}  // namespace
 
-bool use_identities(const View& v) { return uint64_t(v.N) * v.N * v.W / 2 <= kIdPairWordsMax; }
-
-// Shape classes for k_combine (on: the identity route counted case (c)).
+// Shape classes for the combine kernels (on: the identity route counted case (c)).
 IdShapes id_shapes(bool on) {
   const ClassTables& t = class_tables();
   IdShapes sh;
@@ -310,6 +290,8 @@ IdShapes id_shapes(bool on) {
   sh.clique = t.lut4[kPairBits4];
   return sh;
 }
+
+namespace {
 
 // The fused counting launch of a graph with adjacency bit rows, adding to the
 // kHistCopies counter copies at hist (main, sub and G2 regions, or the
@@ -327,7 +309,7 @@ bool launch_bits_count(const hm_graph* H, int k, const uint8_t* lut, unsigned lo
   if (k == 4) {
     const size_t rows = (size_t(v.N) * v.W + 3 * (size_t(v.N) + 1)) * 4;
     const bool lb = rows <= kLdsBitsMaxBytes;
-    const bool id = use_identities(v);
+    const bool id = use_identities(v.N, v.W);
     const size_t lds = size_t(kExact4Waves) * b4_set_words(v.W) * 4 + (lb ? rows : 0);
     const uint64_t items = n2 + (id ? v.N : 0) + n3 + (n4 + kA4Chunk - 1) / kA4Chunk;
     const void* kern = lb ? (id ? reinterpret_cast<const void*>(k_exact4_bits<true, true>)

@@ -405,8 +405,37 @@ __device__ inline void id_node_item(const View& v, uint32_t u, IdAcc& acc) {
   }
 }
 
+// The identity route runs while the node items' codegrees (every node pair,
+// W words each) stay within this many word operations.
+constexpr uint64_t kIdPairWordsMax = 1ull << 28;
+
+__host__ __device__ inline bool use_identities(uint32_t N, uint32_t W) {
+  return uint64_t(N) * N * W / 2 <= kIdPairWordsMax;
+}
+
+// Classes of the six connected 4-node graphs; with `on`, their G2 counts come
+// from the seven identity sums rather than from the G2 region.
+struct IdShapes {
+  int on;
+  int path, star, cycle, paw, diamond, clique;
+};
+
+// Induced count of class c's pairwise shape from the seven sums (0 for a
+// class that is not one of the six shapes): each shape's copies inside the
+// larger shapes are subtracted, largest first.
+__device__ inline unsigned long long id_shape_count(const unsigned long long* ids, const IdShapes& sh, int c) {
+  const unsigned long long T = ids[0] / 3, k4 = ids[4];
+  const unsigned long long dia = ids[2] - 6 * k4;
+  const unsigned long long cyc = ids[5] / 2 - dia - 3 * k4;
+  const unsigned long long paw = ids[3] / 2 - 4 * dia - 12 * k4;
+  const unsigned long long star = ids[6] - paw - 2 * dia - 4 * k4;
+  const unsigned long long path = (ids[1] - 3 * T) - 4 * cyc - 2 * paw - 6 * dia - 12 * k4;
+  return c == sh.clique ? k4 : c == sh.diamond ? dia : c == sh.cycle ? cyc : c == sh.paw ? paw
+         : c == sh.star ? star : c == sh.path ? path : 0ull;
+}
+
 // Reduce the sums over the wavefront and add them to the seven counters at
-// h_acc (LDS); every lane of the wavefront must call this.
+// h_acc (LDS or device memory); every lane of the wavefront must call this.
 __device__ inline void id_flush(const IdAcc& a, unsigned long long* h_acc) {
   const unsigned long long s[7] = {wave_sum(a.t3), wave_sum(a.p4),   wave_sum(a.dia), wave_sum(a.paw2),
                                    wave_sum(a.k4), wave_sum(a.c4x2), wave_sum(a.star)};

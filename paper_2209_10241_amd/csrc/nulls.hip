@@ -40,6 +40,7 @@
 namespace hm {
 
 int count_exact_impl(const hm_graph* H, int k, int64_t* counts, hipStream_t st);
+IdShapes id_shapes(bool on);
 int sampled_with_sizes(const hm_graph* H, int k, const uint64_t S[5], uint64_t seed, float* est, int64_t* raw,
                        hipStream_t st);
 
@@ -766,12 +767,19 @@ struct Chunks {
   uint32_t per_tile[3];   // items per tile of each phase
 };
 
+// Per copy: kMain, kSub and kG2 regions, then the seven identity sums.
+constexpr uint32_t kNullHistStride = kIdAcc + 16;
+
+// With the identity route (order 4 with bit rows), phase 1 of a copy takes
+// its pairs, then one item per node.
+__device__ inline bool batch_ident(const BatchView& b, int k) { return k == 4 && b.bits && use_identities(b.N, b.W); }
+
 __global__ void k_tile_counts(uint32_t R, int k, BatchView b, Chunks ch, uint32_t* counts) {
   for (uint32_t s = blockIdx.x * blockDim.x + threadIdx.x; s < 3 * R; s += gridDim.x * blockDim.x) {
     const uint32_t ph = s / R, c = s % R;
     uint32_t items = 0;
     if (ph == 0) items = k == 4 ? b.base3[c + 1] - b.base3[c] : 0;
-    if (ph == 1) items = b.base2[c + 1] - b.base2[c];
+    if (ph == 1) items = b.base2[c + 1] - b.base2[c] + (batch_ident(b, k) ? b.N : 0u);
     if (ph == 2) items = k == 4 ? b.base4[c + 1] - b.base4[c] : b.base3[c + 1] - b.base3[c];
     counts[s] = (items + ch.per_tile[ph] - 1) / ch.per_tile[ph];
   }
@@ -808,7 +816,7 @@ __global__ void __launch_bounds__(kThreads) k_null_count(BatchView b, uint32_t R
     const uint32_t ph = lo / R, c = lo % R;
     const uint32_t first = (t - tile_prefix[lo]) * ch.per_tile[ph];
     const View v = copy_view(b, c);
-    unsigned long long* hc = hist_all + uint64_t(c) * kHistWords;
+    unsigned long long* hc = hist_all + uint64_t(c) * kNullHistStride;
     for (uint32_t i = lane; i < 512; i += kWave) wh[wv][i] = 0;
     wave_sync();
     if (ph == 0) {
@@ -816,9 +824,23 @@ __global__ void __launch_bounds__(kThreads) k_null_count(BatchView b, uint32_t R
       const uint32_t last = min(n, first + ch.per_tile[0]);
       for (uint32_t j = first; j < last; ++j) b4_item(v, b.base3[c] + j, b4_sets + wv * b4_set_words(b.W), lut, h_main, h_sub);
     } else if (ph == 1) {
-      const uint32_t n = b.base2[c + 1] - b.base2[c];
+      const uint32_t n2c = b.base2[c + 1] - b.base2[c];
+      const bool id = batch_ident(b, k);
+      const uint32_t n = n2c + (id ? b.N : 0u);
       const uint32_t last = min(n, first + ch.per_tile[1]);
-      if (k == 4) {
+      if (id) {
+        IdAcc acc;
+        id_zero(acc);
+        for (uint32_t j = first; j < last; ++j) {
+          if (j < n2c) {
+            const uint64_t q = b.base2[c] + j;
+            id_edge_item(v, b.e2[2 * q], b.e2[2 * q + 1], L, ylist[wv], acc);
+          } else {
+            id_node_item(v, j - n2c, acc);
+          }
+        }
+        id_flush(acc, hc + kIdAcc);
+      } else if (k == 4) {
         if (v.bits) {
           C4Acc acc;
           c4_zero(acc);
@@ -886,13 +908,14 @@ struct ClassMaskB {
 };
 
 __global__ void k_b_combine(const unsigned long long* __restrict__ hist_all, int n_classes, ClassMaskB pairs_only,
-                            int64_t* __restrict__ counts) {
+                            IdShapes sh, int64_t* __restrict__ counts) {
   const uint32_t c = blockIdx.x;
   const int m = threadIdx.x;
   if (m >= n_classes) return;
-  const unsigned long long* h = hist_all + uint64_t(c) * kHistWords;
+  const unsigned long long* h = hist_all + uint64_t(c) * kNullHistStride;
   unsigned long long v = h[kMain + m];
-  if ((pairs_only.w[m >> 6] >> (m & 63)) & 1ull) v += h[kG2 + m] - h[kSub + m];
+  if ((pairs_only.w[m >> 6] >> (m & 63)) & 1ull)
+    v += (sh.on ? id_shape_count(h + kIdAcc, sh, m) : h[kG2 + m]) - h[kSub + m];
   counts[uint64_t(c) * n_classes + m] = int64_t(v);
 }
 
@@ -1078,7 +1101,7 @@ int make_plan(const hm_graph* H, int k, uint32_t R, int model, int sweeps, NullP
   GET(P->i4_off, RN + 1);
   GET(P->i4_idx, 4 * m4);
   if (P->use_bits) GET(P->bits, RN * P->W);
-  GET(P->hist_all, uint64_t(R) * kHistWords);
+  GET(P->hist_all, uint64_t(R) * kNullHistStride);
   GET(P->tile_counts, 3ull * R + 1);
   GET(P->tile_prefix, 3ull * R + 1);
   GET(P->tile_counter, 1);
@@ -1214,7 +1237,7 @@ int enqueue_count(const hm_graph* H, NullPlan& P, const Chunks& ch, hipStream_t 
   k_tile_counts<<<grid_for(3ull * R), 256, 0, st>>>(R, P.k, bv, ch, P.tile_counts);
   HM_HIP(hipGetLastError());
   HM_TRY(scan_u32_ws(P.tile_counts, P.tile_prefix, 3ull * R, P.tile_prefix + 3ull * R, P.scan_ws, st));
-  HM_TRY(fill_u64(P.hist_all, 0, uint64_t(R) * kHistWords, st));
+  HM_TRY(fill_u64(P.hist_all, 0, uint64_t(R) * kNullHistStride, st));
   HM_TRY(fill_u32(P.tile_counter, 0, 1, st));
   const size_t lds = (P.k == 4 && bv.bits) ? size_t(kWavesPerBlock) * b4_set_words(bv.W) * 4 : 0;
   k_null_count<<<persistent_grid(lds), kThreads, lds, st>>>(bv, R, P.k, P.tile_prefix, P.tile_counter, ch,
@@ -1224,7 +1247,8 @@ int enqueue_count(const hm_graph* H, NullPlan& P, const Chunks& ch, hipStream_t 
   ClassMaskB pairs_only{{0, 0, 0, 0}};
   for (int c = 0; c < t.n_classes[P.k]; ++c)
     if (t.maxcard[P.k][c] == 2) pairs_only.w[c >> 6] |= 1ull << (c & 63);
-  k_b_combine<<<R, 256, 0, st>>>(P.hist_all, t.n_classes[P.k], pairs_only, P.nulls);
+  k_b_combine<<<R, 256, 0, st>>>(P.hist_all, t.n_classes[P.k], pairs_only,
+                                 id_shapes(P.k == 4 && P.use_bits && use_identities(P.N, P.W)), P.nulls);
   HM_HIP(hipGetLastError());
   return HM_OK;
 }
