@@ -172,6 +172,94 @@ __global__ void __launch_bounds__(kThreads) k_sp_c4(View v, uint32_t* __restrict
   block_add(total, acc + kAccC4);
 }
 
+// 4-cycles without atomics per wedge: every wedge (u, x, w) with x and w
+// before the top node u in degree order becomes the key (u << B) | w; sorted,
+// each run of equal keys holds the middle nodes of one (u, w) and adds
+// C(run, 2) cycles.  Each pair {x, u} of G2 (x the earlier) walks the row of x,
+// so the walked positions are laid out flat, pair after pair, and cut into
+// tiles of kC4Tile positions that span at most kC4Tile + 1 pairs (every row
+// walked is non-empty).  Positions that are not wedges get the key kC4None.
+constexpr unsigned long long kC4None = ~0ull;
+constexpr uint32_t kC4Tile = 2048;
+
+// Walked positions of each pair (the degree of its earlier node) and their sum.
+__global__ void k_c4_len(View v, uint64_t n2, uint32_t* __restrict__ len, unsigned long long* __restrict__ total) {
+  unsigned long long s = 0;
+  for (uint64_t e = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < n2; e += uint64_t(gridDim.x) * blockDim.x) {
+    const uint32_t a = v.e2[2 * e], b = v.e2[2 * e + 1];
+    const uint32_t d = deg2_of(v, rank_less(v, a, b) ? a : b);
+    len[e] = d;
+    s += d;
+  }
+  block_add(s, total);
+}
+
+// The pair that holds the first position of each tile (pos = exclusive scan of len).
+__global__ void k_c4_tile_starts(const uint32_t* __restrict__ pos, const uint32_t* __restrict__ len, uint64_t n2,
+                                 uint32_t* __restrict__ start) {
+  for (uint64_t e = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < n2; e += uint64_t(gridDim.x) * blockDim.x) {
+    const uint64_t lo = pos[e], hi = lo + len[e];
+    for (uint64_t t = (lo + kC4Tile - 1) / kC4Tile; t * kC4Tile < hi; ++t) start[t] = uint32_t(e);
+  }
+}
+
+// One workgroup per tile: the tile's pairs are staged in LDS (start offset,
+// top node, row of the earlier node) and each position finds its pair there.
+__global__ void __launch_bounds__(kThreads) k_c4_keys(View v, int B, const uint32_t* __restrict__ pos,
+                                                      const uint32_t* __restrict__ start, uint64_t n2,
+                                                      uint32_t n_pos, uint32_t n_tiles,
+                                                      unsigned long long* __restrict__ keys) {
+  __shared__ uint32_t s_pos[kC4Tile + 2], s_top[kC4Tile + 2], s_row[kC4Tile + 2];
+  const uint32_t tid = threadIdx.x, t = blockIdx.x;
+  const uint32_t p0 = t * kC4Tile;
+  const uint32_t p1 = n_pos - p0 < kC4Tile ? n_pos : p0 + kC4Tile;
+  const uint32_t c0 = start[t];
+  const uint32_t c1 = t + 1 < n_tiles ? start[t + 1] : uint32_t(n2 - 1);
+  const uint32_t cnt = c1 - c0 + 1;   // at most kC4Tile + 1
+  for (uint32_t i = tid; i < cnt; i += kThreads) {
+    const uint32_t e = c0 + i, a = v.e2[2 * uint64_t(e)], b = v.e2[2 * uint64_t(e) + 1];
+    const bool ab = rank_less(v, a, b);
+    s_pos[i] = pos[e];
+    s_top[i] = ab ? b : a;
+    s_row[i] = v.g2_off[ab ? a : b];
+  }
+  __syncthreads();
+  for (uint32_t p = p0 + tid; p < p1; p += kThreads) {
+    uint32_t lo = 0, hi = cnt;   // s_pos[lo] <= p < s_pos[hi]
+    while (hi - lo > 1) {
+      const uint32_t m = (lo + hi) >> 1;
+      if (s_pos[m] <= p) lo = m; else hi = m;
+    }
+    const uint32_t u = s_top[lo], w = v.g2_adj[s_row[lo] + (p - s_pos[lo])];
+    keys[p] = (w == u || !rank_less(v, w, u)) ? kC4None : ((unsigned long long)u << B) | (unsigned long long)w;
+  }
+}
+
+// Sum of C(run, 2) over the runs of equal keys (kC4None excluded) of the
+// sorted keys[0, n).
+__global__ void k_c4_runs(const unsigned long long* __restrict__ keys, uint64_t n, unsigned long long none,
+                          unsigned long long* __restrict__ acc) {
+  unsigned long long s = 0;
+  for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += uint64_t(gridDim.x) * blockDim.x) {
+    const unsigned long long key = keys[i];
+    if (key == none || (i > 0 && keys[i - 1] == key)) continue;
+    uint64_t lo = i, hi = n;   // keys[lo] == key, keys[hi] != key (or hi = n)
+    while (hi - lo > 1) {
+      const uint64_t m = lo + ((hi - lo) >> 1);
+      if (keys[m] == key) lo = m; else hi = m;
+    }
+    const unsigned long long run = hi - i;
+    s += run * (run - 1) / 2;
+  }
+  block_add(s, acc);
+}
+
+int node_bits_of(uint32_t n) {
+  int b = 1;
+  while (b < 32 && (1ull << b) < n) ++b;
+  return b;
+}
+
 // Neighbours that follow each node in degree order (outdeg zeroed by the caller).
 __global__ void k_sp_outdeg(View v, uint64_t n2, uint32_t* __restrict__ outdeg) {
   for (uint64_t e = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < n2; e += uint64_t(gridDim.x) * blockDim.x) {
@@ -852,16 +940,50 @@ int count_sparse(const hm_graph* H, int k, hipStream_t st) {
   cls.diamond = t.lut4[(1u << 0) | (1u << 1) | (1u << 2) | (1u << 4) | (1u << 5)];
   cls.clique = t.lut4[kPairBits4];
   if (k == 4 && n2) {
-    // 4-cycles
-    // workgroups, each with 8 bytes of counters per node: at most about 2 GiB
-    const unsigned g = grid_cap(H->n_nodes, 1, unsigned(std::max<uint64_t>(64, std::min<uint64_t>(1024, (1ull << 28) / std::max<uint32_t>(H->n_nodes, 1)))));
-    uint32_t *cnt = nullptr, *touched = nullptr;
-    HM_TRY(tmp.get(&cnt, uint64_t(g) * H->n_nodes));
-    HM_TRY(tmp.get(&touched, uint64_t(g) * H->n_nodes));
-    HM_TRY(fill_u32(cnt, 0, uint64_t(g) * H->n_nodes, st));
-    {
-      ProfileScope ps("k_sp_c4", st);
-      k_sp_c4<false><<<g, kThreads, 0, st>>>(v, cnt, touched, acc, nullptr, nullptr);
+    // 4-cycles: wedge keys, sorted, counted by runs
+    unsigned long long* walk = nullptr;
+    uint32_t *len = nullptr, *pos = nullptr;
+    HM_TRY(tmp.get(&walk, 1));
+    HM_TRY(tmp.get(&len, n2));
+    HM_TRY(tmp.get(&pos, n2));
+    HM_TRY(fill_u64(walk, 0, 1, st));
+    k_c4_len<<<grid_cap(n2, 256, 2048), 256, 0, st>>>(v, n2, len, walk);
+    HM_HIP(hipGetLastError());
+    unsigned long long n_keys = 0;
+    HM_HIP(hipMemcpyAsync(&n_keys, walk, sizeof(n_keys), hipMemcpyDeviceToHost, st));
+    HM_HIP(hipStreamSynchronize(st));
+    const int B = node_bits_of(H->n_nodes);
+    if (n_keys >= 0xFFFFFFFFull || 2 * B > 63 || n2 >= 0xFFFFFFFFull) {
+      set_error("4-cycle wedges of %llu positions exceed the sort's range", n_keys);
+      return HM_EUNSUPPORTED;
+    }
+    if (n_keys) {
+      const uint32_t n_tiles = uint32_t((n_keys + kC4Tile - 1) / kC4Tile);
+      unsigned long long *keys = nullptr, *keys_tmp = nullptr;
+      uint32_t *vals = nullptr, *vals_tmp = nullptr, *start = nullptr;
+      HM_TRY(tmp.get(&start, n_tiles));
+      HM_TRY(tmp.get(&keys, n_keys));
+      HM_TRY(tmp.get(&keys_tmp, n_keys));
+      HM_TRY(tmp.get(&vals, n_keys));
+      HM_TRY(tmp.get(&vals_tmp, n_keys));
+      HM_TRY(scan_exclusive_u32(len, pos, n2, nullptr, st));
+      k_c4_tile_starts<<<grid_cap(n2, 256, 4096), 256, 0, st>>>(pos, len, n2, start);
+      HM_HIP(hipGetLastError());
+      {
+        ProfileScope ps("k_c4_keys", st);
+        k_c4_keys<<<n_tiles, kThreads, 0, st>>>(v, B, pos, start, n2, uint32_t(n_keys), n_tiles, keys);
+      }
+      HM_HIP(hipGetLastError());
+      // the positions that are not wedges carry all ones and sort last
+      {
+        ProfileScope ps("c4_sort", st);
+        HM_TRY(radix_sort_pairs(keys, vals, keys_tmp, vals_tmp, n_keys, 2 * B + 1, st));
+      }
+      {
+        ProfileScope ps("k_c4_runs", st);
+        k_c4_runs<<<grid_cap(n_keys, 256, 4096), 256, 0, st>>>(keys, n_keys, kC4None, acc + kAccC4);
+      }
+      HM_HIP(hipGetLastError());
     }
     // 4-cliques
     uint32_t *outdeg = nullptr, *dmax = nullptr;
