@@ -984,7 +984,7 @@ int build(hm_graph* H, const uint32_t* members_in, const uint64_t* offsets_in, u
 void release(hm_graph* H, hipStream_t st = nullptr, bool ordered = false) {
   void* ps[] = {H->e2,     H->e3,      H->e4,     H->all_members, H->all_off, H->hs2.slot, H->hs3.slot,
                 H->hs4.slot, H->g2_off, H->g2_adj, H->g2_eid,      H->i3_off,  H->i3_idx,   H->i4_off,
-                H->i4_idx, H->bits,     H->hist,   H->sample_hist, H->pl_keys, H->pl_edge,  H->pl_slot, H->pl_codeg, H->pl_third, H->pl_adj, H->b4_order, H->hub_rank, H->hub_bits, H->proj_bits, H->ns_tri,
+                H->i4_idx, H->bits,     H->hist,   H->sample_hist, H->pl_keys, H->pl_edge,  H->pl_slot, H->pl_codeg, H->pl_third, H->pl_adj, H->pl_pre, H->q_slot, H->q_fourth, H->b4_order, H->hub_rank, H->hub_bits, H->proj_bits, H->ns_tri,
                 H->ns_nbr, H->ns_h3,    H->es,         H->e5,      H->hs5};
   constexpr size_t n = sizeof(ps) / sizeof(ps[0]);
   if (ordered) {

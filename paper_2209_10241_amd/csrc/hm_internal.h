@@ -276,6 +276,12 @@ struct hm_graph {
   // adjacency to the pair's two nodes (bits 0 and 1)
   uint32_t* pl_third = nullptr;
   uint8_t* pl_adj = nullptr;
+  uint32_t* pl_pre = nullptr;
+  // 3-node subset -> 4-node hyperedges (see quad_find; q_bits = 0: not built)
+  unsigned long long* q_slot = nullptr;
+  unsigned long long q_mask = 0;
+  uint32_t* q_fourth = nullptr;
+  int q_bits = 0;   // 4 x (entries + 1) prefix counts by adjacency class
   // the 3-node hyperedges by decreasing estimated cost of their exact
   // neighbourhood count (built on first use without bit rows)
   uint32_t* b4_order = nullptr;

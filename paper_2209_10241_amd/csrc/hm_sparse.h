@@ -40,6 +40,18 @@ struct PairLinks {
   // adjacency to the key's nodes (bit 0: x ~ t, bit 1: y ~ t)
   const uint32_t* third;
   const uint8_t* adj;
+  // entries of a run are in ascending third node; pre[c * (n + 1) + p] is the
+  // number of entries before position p whose adj is c (c = 0..3)
+  const uint32_t* pre;
+  // 4-node hyperedges by their 3-node subsets: for a < b < c, the run of the
+  // key (a << 2q) | (b << q) | c (q = q_bits) in q_slot lists the fourth
+  // nodes (q_fourth) of the 4-node hyperedges holding {a, b, c}; q_bits = 0
+  // when not built (node ids too wide), and then the 4-node incidence list of
+  // a member is walked instead
+  const ulonglong2* q_slot;
+  unsigned long long q_mask;
+  const uint32_t* q_fourth;
+  int q_bits;
   // dense adjacency rows of the highest-degree nodes: hub_rank[v] is v's row
   // (hub_w words at hub_bits + row * hub_w) or -1; hub_rank null: none
   const int32_t* hub_rank;
@@ -74,6 +86,27 @@ __device__ inline void pl_find(const PairLinks& pl, unsigned long long key, uint
 
 // The number of common pairwise neighbours of x < y, a pair inside some
 // 3-node hyperedge (so present in the index).
+// Run [*lo, *lo + *len) of q_fourth: the fourth nodes of the 4-node
+// hyperedges holding {a < b < c} (pl.q_bits != 0).
+__device__ inline void quad_find(const PairLinks& pl, uint32_t a, uint32_t b, uint32_t c, uint64_t* lo,
+                                 uint32_t* len) {
+  const int q = pl.q_bits;
+  const unsigned long long key = ((unsigned long long)a << (2 * q)) | ((unsigned long long)b << q) | c;
+  *lo = 0;
+  *len = 0;
+  unsigned long long h = mix64(key) & pl.q_mask;
+  while (true) {
+    const ulonglong2 s = pl.q_slot[h];
+    if (s.x == key) {
+      *lo = s.y >> 32;
+      *len = uint32_t(s.y);
+      return;
+    }
+    if (s.x == kEmpty64) return;
+    h = (h + 1) & pl.q_mask;
+  }
+}
+
 __device__ inline uint32_t pl_codeg(const PairLinks& pl, uint32_t x, uint32_t y) {
   const unsigned long long key = ((unsigned long long)x << 32) | y;
   unsigned long long h = mix64(key) & pl.mask;
@@ -109,7 +142,8 @@ __device__ inline uint32_t row_count(const View& v, uint32_t s, uint32_t x) {
 
 // The hyperedge e = {a<b<c} with its pairwise pattern and the ranges of its
 // exceptional nodes: slot 0..2 the pair index entries of {a,b}, {a,c},
-// {b,c}; slot 3 the 4-node hyperedges of the member with the fewest of them.
+// {b,c}; slot 3 the fourth nodes of the 4-node hyperedges holding e (with
+// pl.q_bits), else the 4-node hyperedges of the member with the fewest.
 struct B4Ctx {
   uint32_t a, b, c, base_p;
   int ra, rb, rc;   // dense adjacency rows of a, b, c, or -1
@@ -132,11 +166,17 @@ __device__ __forceinline__ B4Ctx b4_ctx(const View& v, const PairLinks& pl, uint
   x.len0 = l0;
   x.len1 = l1;
   x.len2 = l2;
-  const uint32_t fa = v.i4_off[a + 1] - v.i4_off[a], fb = v.i4_off[b + 1] - v.i4_off[b],
-                 fc = v.i4_off[c + 1] - v.i4_off[c];
-  const uint32_t m4 = (fa <= fb && fa <= fc) ? a : (fb <= fc ? b : c);
-  x.lo3 = v.i4_off[m4];
-  x.len3 = v.i4_off[m4 + 1] - x.lo3;
+  if (pl.q_bits) {
+    uint32_t l3;
+    quad_find(pl, a, b, c, &x.lo3, &l3);
+    x.len3 = l3;
+  } else {
+    const uint32_t fa = v.i4_off[a + 1] - v.i4_off[a], fb = v.i4_off[b + 1] - v.i4_off[b],
+                   fc = v.i4_off[c + 1] - v.i4_off[c];
+    const uint32_t m4 = (fa <= fb && fa <= fc) ? a : (fb <= fc ? b : c);
+    x.lo3 = v.i4_off[m4];
+    x.len3 = v.i4_off[m4 + 1] - x.lo3;
+  }
   x.ra = int(uniform_u32(uint32_t(hub_of(pl, a))));
   x.rb = int(uniform_u32(uint32_t(hub_of(pl, b))));
   x.rc = int(uniform_u32(uint32_t(hub_of(pl, c))));
@@ -277,7 +317,10 @@ __device__ __forceinline__ B4Short b4_short(const View& v, const PairLinks& pl, 
   if (x.len3 <= kWave) {
     bool hold = false;
     uint32_t y = 0;
-    if (lane < x.len3) {
+    if (lane < x.len3 && pl.q_bits) {
+      hold = true;
+      y = pl.q_fourth[x.lo3 + lane];
+    } else if (lane < x.len3) {
       const uint32_t* f = v.e4 + 4ull * v.i4_idx[x.lo3 + lane];
       const uint32_t f0 = f[0], f1 = f[1], f2 = f[2], f3 = f[3];
       const uint32_t hit = uint32_t(f0 == x.a || f0 == x.b || f0 == x.c) + uint32_t(f1 == x.a || f1 == x.b || f1 == x.c) +
@@ -304,35 +347,22 @@ __device__ __forceinline__ B4Short b4_short(const View& v, const PairLinks& pl, 
 // bit 3 set when its set counts (not a 4-node hyperedge and, with OWN, e its
 // smallest 3-node hyperedge), with the set's pattern in *pat.  With sh, the
 // lists it holds replace the corresponding probes.
+//
+// b4_exception_node takes the node itself: y with its slot (0..2: the third
+// node of a 3-node hyperedge on pair {a,b}, {a,c} or {b,c} of e, pair_adj its
+// pairwise adjacency to that pair's lower and higher node in bits 0 and 1;
+// 3: the fourth node of a 4-node hyperedge holding e, pair_adj unused).
 template <bool OWN>
-__device__ __forceinline__ uint32_t b4_exception(const View& v, const PairLinks& pl, const B4Ctx& x, uint64_t t,
-                                        uint32_t* pat, const B4Short& sh) {
+__device__ __forceinline__ uint32_t b4_exception_node(const View& v, const PairLinks& pl, const B4Ctx& x, int slot,
+                                                      uint32_t y, uint32_t pair_adj, uint32_t* pat,
+                                                      const B4Short& sh) {
   const uint32_t a = x.a, b = x.b, c = x.c;
   const bool hab = sh.n_ab != kB4NotHeld, hac = sh.n_ac != kB4NotHeld, hbc = sh.n_bc != kB4NotHeld,
              hq = sh.n_q != kB4NotHeld;
   const bool ha = sh.n_a != kB4NotHeld, hb = sh.n_b != kB4NotHeld, hc = sh.n_c != kB4NotHeld;
   const int ra = x.ra, rb = x.rb, rc = x.rc;
-  // slot and offset of t, with constant indices only (registers)
-  int slot;
-  uint64_t p;
-  if (t < x.len0) {
-    slot = 0;
-    p = x.lo0 + t;
-  } else if (t < x.len0 + x.len1) {
-    slot = 1;
-    p = x.lo1 + (t - x.len0);
-  } else if (t < x.len0 + x.len1 + x.len2) {
-    slot = 2;
-    p = x.lo2 + (t - x.len0 - x.len1);
-  } else {
-    slot = 3;
-    p = x.lo3 + (t - x.len0 - x.len1 - x.len2);
-  }
-  uint32_t y, pair_adj = 0;
   if (slot < 3) {
-    y = pl.third[p];
     if (y == a || y == b || y == c) return 0;   // e itself
-    pair_adj = pl.adj[p];
     // The slot's own 3-node hyperedge {y} u pair comes after e only when y is
     // above m, the member of e outside the pair (c, b, a for slots 0, 1, 2).
     // Otherwise e is not the smallest 3-node hyperedge of e u {y}, so with
@@ -360,13 +390,6 @@ __device__ __forceinline__ uint32_t b4_exception(const View& v, const PairLinks&
       const uint32_t cv = slot == 0 ? mv : hi;
       return 16u | av | (bv << 1) | (cv << 2);
     }
-  } else {
-    const uint32_t* f = v.e4 + 4ull * v.i4_idx[p];
-    const uint32_t f0 = f[0], f1 = f[1], f2 = f[2], f3 = f[3];
-    const uint32_t hit = uint32_t(f0 == a || f0 == b || f0 == c) + uint32_t(f1 == a || f1 == b || f1 == c) +
-                         uint32_t(f2 == a || f2 == b || f2 == c) + uint32_t(f3 == a || f3 == b || f3 == c);
-    if (hit != 3) return 0;
-    y = f0 ^ f1 ^ f2 ^ f3 ^ a ^ b ^ c;
   }
   // Every membership test the set e u {y} needs, issued together: the
   // 3-node sets through y not already known from the slot, the 4-node set
@@ -430,6 +453,33 @@ __device__ __forceinline__ uint32_t b4_exception(const View& v, const PairLinks&
   return 16u | (counted ? 8u : 0u) | combo;
 }
 
+template <bool OWN>
+__device__ __forceinline__ uint32_t b4_exception(const View& v, const PairLinks& pl, const B4Ctx& x, uint64_t t,
+                                                 uint32_t* pat, const B4Short& sh) {
+  // slot and offset of t, with constant indices only (registers)
+  if (t < x.len0) {
+    const uint64_t p = x.lo0 + t;
+    return b4_exception_node<OWN>(v, pl, x, 0, pl.third[p], pl.adj[p], pat, sh);
+  }
+  if (t < x.len0 + x.len1) {
+    const uint64_t p = x.lo1 + (t - x.len0);
+    return b4_exception_node<OWN>(v, pl, x, 1, pl.third[p], pl.adj[p], pat, sh);
+  }
+  if (t < x.len0 + x.len1 + x.len2) {
+    const uint64_t p = x.lo2 + (t - x.len0 - x.len1);
+    return b4_exception_node<OWN>(v, pl, x, 2, pl.third[p], pl.adj[p], pat, sh);
+  }
+  if (pl.q_bits) return b4_exception_node<OWN>(v, pl, x, 3, pl.q_fourth[x.lo3 + (t - x.len0 - x.len1 - x.len2)], 0u,
+                                              pat, sh);
+  const uint32_t* f = v.e4 + 4ull * v.i4_idx[x.lo3 + (t - x.len0 - x.len1 - x.len2)];
+  const uint32_t f0 = f[0], f1 = f[1], f2 = f[2], f3 = f[3];
+  const uint32_t a = x.a, b = x.b, c = x.c;
+  const uint32_t hit = uint32_t(f0 == a || f0 == b || f0 == c) + uint32_t(f1 == a || f1 == b || f1 == c) +
+                       uint32_t(f2 == a || f2 == b || f2 == c) + uint32_t(f3 == a || f3 == b || f3 == c);
+  if (hit != 3) return 0;
+  return b4_exception_node<OWN>(v, pl, x, 3, f0 ^ f1 ^ f2 ^ f3 ^ a ^ b ^ c, 0u, pat, sh);
+}
+
 // The combination pattern of e u {v} for a non-exceptional v.
 __device__ inline uint32_t b4_combo_pattern(const B4Ctx& x, uint32_t cmb) {
   return x.base_p | ((cmb & 1u) << 4) | (((cmb >> 1) & 1u) << 5) | ((cmb >> 2) << 7);
@@ -439,7 +489,8 @@ __device__ inline uint32_t b4_combo_pattern(const B4Ctx& x, uint32_t cmb) {
 // wavefront per hyperedge.
 template <bool OWN>
 __device__ void b4_sparse(const View& v, const PairLinks& pl, uint32_t a, uint32_t b, uint32_t c, const uint8_t* lut,
-                          unsigned long long* h_main, unsigned long long* h_sub, uint32_t* short_mem = nullptr) {
+                          unsigned long long* h_main, unsigned long long* h_sub, uint32_t* short_mem = nullptr,
+                          bool runs = true) {
   const int lane = threadIdx.x & (kWave - 1);
   const B4Ctx x = b4_ctx(v, pl, a, b, c);
   uint32_t n[8];
@@ -448,7 +499,10 @@ __device__ void b4_sparse(const View& v, const PairLinks& pl, uint32_t a, uint32
   // exceptional nodes, in one lane-strided range; per lane, the number of
   // them in each pairwise combination
   uint32_t dn1 = 0, dn2 = 0, dn3 = 0, dn4 = 0, dn5 = 0, dn6 = 0, dn7 = 0;
-  for (uint64_t t = lane; t < x.total; t += kWave) {
+  // without `runs`, the positions of the pair runs (slots 0..2) are left to
+  // the pair-run pass (b4_run_entry), which adds their terms itself
+  const uint64_t t0 = runs ? 0 : x.len0 + x.len1 + x.len2;
+  for (uint64_t t = t0 + lane; t < x.total; t += kWave) {
     uint32_t pat;
     const uint32_t r = b4_exception<OWN>(v, pl, x, t, &pat, sh);
     if (!r) continue;
@@ -492,6 +546,214 @@ __device__ void b4_sparse(const View& v, const PairLinks& pl, uint32_t a, uint32
         if (g != 0xFF) atomicAdd(&h_sub[g], (unsigned long long)n[cmb]);
       }
     }
+  }
+}
+
+// Position of node z among the third nodes of the run [lo, lo + len) (sorted),
+// or ~0 when absent.
+__device__ inline uint64_t run_find(const PairLinks& pl, uint64_t lo, uint32_t len, uint32_t z) {
+  uint64_t l = lo, h = lo + len;   // pl.third[l..h) may hold z
+  while (h > l) {
+    const uint64_t m = l + ((h - l) >> 1);
+    const uint32_t y = pl.third[m];
+    if (y == z) return m;
+    if (y < z) l = m + 1; else h = m;
+  }
+  return ~0ull;
+}
+
+// The pair-run terms of exact counting for entry p of the pair index: the
+// 3-node hyperedge e = {x, y, t} (pair {x < y} of the entry's key, t its
+// third node) against every other entry z of the same run, which are the
+// positions of one slot of e's exception walk (slot 0, 1, 2 when the pair is
+// {a,b}, {a,c}, {b,c} of e).  Every lane of the wavefront calls this.
+//
+// An entry z related to t in none of four ways (z a pairwise neighbour of t;
+// {x,t,z} or {y,t,z} a 3-node hyperedge; {x,y,t,z} a 4-node hyperedge) has
+// an outcome fixed by z's adjacency class to the pair (bits lo, hi) and by
+// whether z < t: below t it is one more node of its combination (e does not
+// own the set, whose 3-node hyperedge {x,y,z} precedes e); above t it is also
+// counted once, its pattern holding e's pattern, z's two pairs and the
+// 3-node hyperedge of the slot's pair.  Those are counted from the run's
+// prefix counts by class.  The related entries are listed from t's side (its
+// pairwise row, the runs of {x,t} and {y,t}, the 4-node hyperedges holding
+// e; each node from the first list that holds it) and classified one by one
+// as the exception walk does; when the run is not longer than those lists,
+// the run itself is walked instead.
+__device__ void b4_run_entry(const View& v, const PairLinks& pl, uint64_t p, const uint8_t* lut,
+                             unsigned long long* h_main, unsigned long long* h_sub) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const unsigned long long key = pl.keys[p];
+  const bool alone = (p == 0 || pl.keys[p - 1] != key) && (p + 1 == pl.n || pl.keys[p + 1] != key);
+  if (alone) return;   // no other entry in the run
+  const uint32_t px = uint32_t(key >> 32), py = uint32_t(key), t = pl.third[p];
+  const int slot = t > py ? 0 : (t > px ? 1 : 2);
+  const uint32_t a = slot == 2 ? t : px, b = slot == 0 ? py : (slot == 1 ? t : px), c = slot == 0 ? t : py;
+  // the run of the pair
+  uint64_t lo;
+  uint32_t L;
+  pl_find(pl, key, &lo, &L);
+  lo = uniform_u64(lo);
+  L = uniform_u32(L);
+  const uint32_t t_off = uniform_u32(v.g2_off[t]), dt = uniform_u32(v.g2_off[t + 1]) - t_off;
+  // A run no longer than t's pairwise row is walked whatever the other lists
+  // hold: e's pattern and the members' dense rows are all that walk needs.
+  // Otherwise the runs of {x, t} and {y, t} and the 4-node lists decide.
+  B4Ctx x;
+  bool walk_run = uint64_t(L) - 1 <= dt;
+  uint64_t lo_xt = 0, lo_yt = 0;
+  uint32_t len_xt = 0, len_yt = 0;
+  uint64_t listed = dt;
+  if (walk_run) {
+    x.a = a;
+    x.b = b;
+    x.c = c;
+    const uint32_t pp = has2(v.hs2, px, py), cl = pl.adj[p], l = cl & 1u, h = cl >> 1;
+    x.base_p = uniform_u32((slot == 0 ? (pp | (l << 1) | (h << 2)) : (slot == 1 ? (l | (pp << 1) | (h << 2))
+                                                                                 : (l | (h << 1) | (pp << 2)))) |
+                           (1u << 3));
+    x.ra = int(uniform_u32(uint32_t(hub_of(pl, a))));
+    x.rb = int(uniform_u32(uint32_t(hub_of(pl, b))));
+    x.rc = int(uniform_u32(uint32_t(hub_of(pl, c))));
+    x.lo0 = x.lo1 = x.lo2 = x.lo3 = x.len0 = x.len1 = x.len2 = x.len3 = x.total = 0;
+  } else {
+    x = b4_ctx(v, pl, a, b, c);
+    lo_xt = slot == 0 ? x.lo1 : x.lo0;
+    len_xt = uint32_t(slot == 0 ? x.len1 : x.len0);
+    lo_yt = slot == 2 ? x.lo1 : x.lo2;
+    len_yt = uint32_t(slot == 2 ? x.len1 : x.len2);
+    listed = uint64_t(dt) + len_xt + len_yt + x.len3;
+    walk_run = uint64_t(L) - 1 <= listed;
+  }
+  const int rt = slot == 0 ? x.rc : (slot == 1 ? x.rb : x.ra);   // t's dense row, or -1
+  const B4Short sh = b4_short_none();
+  uint32_t dn1 = 0, dn2 = 0, dn3 = 0, dn4 = 0, dn5 = 0, dn6 = 0, dn7 = 0;
+  uint32_t ml0 = 0, ml1 = 0, ml2 = 0, ml3 = 0, mg0 = 0, mg1 = 0, mg2 = 0, mg3 = 0;
+  const uint64_t n_items = walk_run ? L : listed;
+  for (uint64_t q = lane; q < n_items; q += kWave) {
+    uint32_t z, cls;
+    if (walk_run) {
+      if (lo + q == p) continue;
+      z = pl.third[lo + q];
+      cls = pl.adj[lo + q];
+    } else {
+      int src;
+      if (q < dt) {
+        z = v.g2_adj[t_off + q];
+        src = 0;
+      } else if (q < uint64_t(dt) + len_xt) {
+        z = pl.third[lo_xt + (q - dt)];
+        src = 1;
+      } else if (q < uint64_t(dt) + len_xt + len_yt) {
+        z = pl.third[lo_yt + (q - dt - len_xt)];
+        src = 2;
+      } else if (pl.q_bits) {
+        z = pl.q_fourth[x.lo3 + (q - dt - len_xt - len_yt)];
+        src = 3;
+      } else {
+        const uint32_t* f = v.e4 + 4ull * v.i4_idx[x.lo3 + (q - dt - len_xt - len_yt)];
+        const uint32_t f0 = f[0], f1 = f[1], f2 = f[2], f3 = f[3];
+        const uint32_t hit = uint32_t(f0 == a || f0 == b || f0 == c) + uint32_t(f1 == a || f1 == b || f1 == c) +
+                             uint32_t(f2 == a || f2 == b || f2 == c) + uint32_t(f3 == a || f3 == b || f3 == c);
+        if (hit != 3) continue;
+        z = f0 ^ f1 ^ f2 ^ f3 ^ a ^ b ^ c;
+        src = 3;
+      }
+      if (z == px || z == py || z == t) continue;
+      // each related node once, from the first list holding it
+      if (src >= 1 && (rt >= 0 ? hub_adj(pl, rt, z) : uint32_t(has2(v.hs2, t, z)))) continue;
+      if (src >= 2) {
+        uint32_t s0 = px, s1 = t, s2 = z;
+        sort3(s0, s1, s2);
+        if (set128_has(v.hs3, key3(s0, s1, s2))) continue;
+      }
+      if (src >= 3) {
+        uint32_t s0 = py, s1 = t, s2 = z;
+        sort3(s0, s1, s2);
+        if (set128_has(v.hs3, key3(s0, s1, s2))) continue;
+      }
+      const uint64_t j = run_find(pl, lo, L, z);
+      if (j == ~0ull) continue;   // {x, y, z} is not a 3-node hyperedge
+      cls = pl.adj[j];
+      const bool below = z < t;
+      ml0 += below && cls == 0;
+      ml1 += below && cls == 1;
+      ml2 += below && cls == 2;
+      ml3 += below && cls == 3;
+      mg0 += !below && cls == 0;
+      mg1 += !below && cls == 1;
+      mg2 += !below && cls == 2;
+      mg3 += !below && cls == 3;
+    }
+    uint32_t pat;
+    const uint32_t r = b4_exception_node<true>(v, pl, x, slot, z, cls, &pat, sh);
+    if (!r) continue;
+    const uint32_t combo = r & 7u;
+    dn1 += combo == 1;
+    dn2 += combo == 2;
+    dn3 += combo == 3;
+    dn4 += combo == 4;
+    dn5 += combo == 5;
+    dn6 += combo == 6;
+    dn7 += combo == 7;
+    if (!(r & 8u)) continue;
+    atomicAdd(&h_main[lut[pat]], 1ull);
+    const uint8_t g = lut[pat & kPairBits4];
+    if (g != 0xFF) atomicAdd(&h_sub[g], 1ull);
+  }
+  uint32_t dn[8];
+  dn[0] = 0;
+  dn[1] = wave_sum_u32(dn1);
+  dn[2] = wave_sum_u32(dn2);
+  dn[3] = wave_sum_u32(dn3);
+  dn[4] = wave_sum_u32(dn4);
+  dn[5] = wave_sum_u32(dn5);
+  dn[6] = wave_sum_u32(dn6);
+  dn[7] = wave_sum_u32(dn7);
+  uint32_t ml[4] = {0, 0, 0, 0}, mg[4] = {0, 0, 0, 0};
+  if (!walk_run) {
+    ml[0] = wave_sum_u32(ml0);
+    ml[1] = wave_sum_u32(ml1);
+    ml[2] = wave_sum_u32(ml2);
+    ml[3] = wave_sum_u32(ml3);
+    mg[0] = wave_sum_u32(mg0);
+    mg[1] = wave_sum_u32(mg1);
+    mg[2] = wave_sum_u32(mg2);
+    mg[3] = wave_sum_u32(mg3);
+  }
+  if (lane != 0) return;
+  // the unrelated entries, by class, below and above t (constant indices
+  // only, so that the arrays stay in registers)
+  uint32_t all[4] = {0, 0, 0, 0}, cmb_of[4] = {0, 0, 0, 0};
+  if (!walk_run) {
+    const uint64_t n1 = pl.n + 1;
+#pragma unroll
+    for (uint32_t cl = 0; cl < 4; ++cl) {
+      const uint32_t* pre = pl.pre + cl * n1;
+      const uint32_t nl = (pre[p] - pre[lo]) - ml[cl];
+      const uint32_t ng = (pre[lo + L] - pre[p + 1]) - mg[cl];
+      const uint32_t l = cl & 1u, h = cl >> 1;
+      cmb_of[cl] = slot == 0 ? (l | (h << 1)) : (slot == 1 ? (l | (h << 2)) : ((l << 1) | (h << 2)));
+      all[cl] = nl + ng;
+      if (!ng) continue;
+      const uint32_t pat = slot == 0 ? (x.base_p | (l << 4) | (h << 5) | (1u << 6))
+                                     : (slot == 1 ? (x.base_p | (l << 4) | (h << 7) | (1u << 8))
+                                                  : (x.base_p | (l << 5) | (h << 7) | (1u << 9)));
+      atomicAdd(&h_main[lut[pat]], (unsigned long long)ng);
+      const uint8_t g = lut[pat & kPairBits4];
+      if (g != 0xFF) atomicAdd(&h_sub[g], (unsigned long long)ng);
+    }
+  }
+  // every exceptional node of the slot is one fewer of its combination
+#pragma unroll
+  for (uint32_t cmb = 1; cmb < 8; ++cmb) {
+#pragma unroll
+    for (uint32_t cl = 0; cl < 4; ++cl) dn[cmb] += cmb_of[cl] == cmb ? all[cl] : 0u;
+    if (!dn[cmb]) continue;
+    const uint32_t pat = b4_combo_pattern(x, cmb);
+    atomicAdd(&h_main[lut[pat]], 0ull - (unsigned long long)dn[cmb]);
+    const uint8_t g = lut[pat & kPairBits4];
+    if (g != 0xFF) atomicAdd(&h_sub[g], 0ull - (unsigned long long)dn[cmb]);
   }
 }
 

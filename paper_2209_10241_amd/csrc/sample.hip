@@ -1140,6 +1140,11 @@ int launch_sampled(const hm_graph* H, int k, const uint32_t* const idx[5], const
   a.pl.codeg = H->pl_codeg;
   a.pl.third = H->pl_third;
   a.pl.adj = H->pl_adj;
+  a.pl.pre = H->pl_pre;
+  a.pl.q_slot = reinterpret_cast<const ulonglong2*>(H->q_slot);
+  a.pl.q_mask = H->q_mask;
+  a.pl.q_fourth = H->q_fourth;
+  a.pl.q_bits = H->q_bits;
   a.pl.hub_rank = H->hub_rank;
   a.pl.hub_bits = H->hub_bits;
   a.pl.hub_w = H->hub_words;

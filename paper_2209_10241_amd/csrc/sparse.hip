@@ -399,8 +399,28 @@ __global__ void __launch_bounds__(kThreads) k_sp_b4(View v, PairLinks pl, uint64
   uint32_t* short_mem = short_lists[threadIdx.x / kWave];
   for (uint64_t j = wave; j < n3; j += n_waves) {
     const uint64_t i = order[j];
-    b4_sparse<true>(v, pl, v.e3[3 * i], v.e3[3 * i + 1], v.e3[3 * i + 2], lut, h_main, h_sub, short_mem);
+    b4_sparse<true>(v, pl, v.e3[3 * i], v.e3[3 * i + 1], v.e3[3 * i + 2], lut, h_main, h_sub, short_mem, false);
   }
+  __syncthreads();
+  unsigned long long* hc = hist_copy(hist, kExactHistStride);
+  flush(h_main, hc + kMain, 256);
+  flush(h_sub, hc + kSub, 256);
+}
+
+// (b) at order 4 without bit rows, the pair-run terms: one wavefront per
+// entry of the pair index, in index order, so that the entries of one run
+// (and their shared lists) are taken by neighbouring wavefronts.
+__global__ void __launch_bounds__(kThreads) k_sp_b4_runs(View v, PairLinks pl, const uint8_t* __restrict__ lut_g,
+                                                         unsigned long long* __restrict__ hist) {
+  __shared__ uint8_t lut[2048];
+  __shared__ unsigned long long h_main[256], h_sub[256];
+  load_lut(lut, lut_g, 2048);
+  h_main[threadIdx.x] = 0;
+  h_sub[threadIdx.x] = 0;
+  __syncthreads();
+  const uint64_t wave = uint64_t(blockIdx.x) * kWavesPerBlock + threadIdx.x / kWave;
+  const uint64_t n_waves = uint64_t(gridDim.x) * kWavesPerBlock;
+  for (uint64_t p = wave; p < pl.n; p += n_waves) b4_run_entry(v, pl, p, lut, h_main, h_sub);
   __syncthreads();
   unsigned long long* hc = hist_copy(hist, kExactHistStride);
   flush(h_main, hc + kMain, 256);
@@ -409,8 +429,8 @@ __global__ void __launch_bounds__(kThreads) k_sp_b4(View v, PairLinks pl, uint64
 
 // Sort keys of the 3-node hyperedges for k_sp_b4: the complement of an
 // estimate of the memory transactions of each (two per entry of its shortest
-// pairwise row, four per 3-node hyperedge on one of its pairs, six per entry
-// of the 4-node incidence list it reads), with the hyperedge as value.
+// pairwise row, six per entry of the 4-node incidence list it reads when
+// there is no 4-node index), with the hyperedge as value.
 __global__ void k_b4_cost_keys(View v, PairLinks pl, uint64_t n3, unsigned long long* __restrict__ keys,
                                uint32_t* __restrict__ vals) {
   for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n3; i += uint64_t(gridDim.x) * blockDim.x) {
@@ -423,7 +443,11 @@ __global__ void k_b4_cost_keys(View v, PairLinks pl, uint64_t n3, unsigned long 
     const uint64_t dmin = min(deg2_of(v, a), min(deg2_of(v, b), deg2_of(v, c)));
     const uint32_t fa = v.i4_off[a + 1] - v.i4_off[a], fb = v.i4_off[b + 1] - v.i4_off[b],
                    fc = v.i4_off[c + 1] - v.i4_off[c];
-    const uint64_t cost = 2 * dmin + 4 * (uint64_t(lab) + lac + lbc) + 6 * uint64_t(min(fa, min(fb, fc)));
+    (void)lab;
+    (void)lac;
+    (void)lbc;
+    // (with the 4-node index, the 4-node hyperedges holding e are one lookup)
+    const uint64_t cost = 2 * dmin + (pl.q_bits ? 0 : 6 * uint64_t(min(fa, min(fb, fc))));
     keys[i] = 0xFFFFFFFFull - min<uint64_t>(cost, 0xFFFFFFFFull);
     vals[i] = uint32_t(i);
   }
@@ -458,15 +482,39 @@ __global__ void k_sp_shapes(const unsigned long long* __restrict__ acc, int k, S
   hist[kG2 + cls.path] = path;
 }
 
-__global__ void k_pair_link_keys(const uint32_t* __restrict__ e3, uint64_t n3, unsigned long long* __restrict__ keys,
-                                 uint32_t* __restrict__ edge) {
-  for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n3; i += uint64_t(gridDim.x) * blockDim.x) {
-    const unsigned long long a = e3[3 * i], b = e3[3 * i + 1], c = e3[3 * i + 2];
-    keys[3 * i] = (a << 32) | b;
-    keys[3 * i + 1] = (a << 32) | c;
-    keys[3 * i + 2] = (b << 32) | c;
-    edge[3 * i] = edge[3 * i + 1] = edge[3 * i + 2] = uint32_t(i);
+// Entries of the pair index: code 3i + s for 3-node hyperedge i = {a<b<c} and
+// slot s, the pair {a,b} (third node c), {a,c} (b) or {b,c} (a).  The
+// entries are sorted by third node, then stably by pair, so that each pair's
+// run lists its third nodes in ascending order.
+__device__ inline uint32_t pl_third_of(const uint32_t* e3, uint32_t code) {
+  const uint64_t i = code / 3;
+  const uint32_t s = code % 3;
+  return e3[3 * i + 2 - s];
+}
+
+__global__ void k_pl_third_keys(const uint32_t* __restrict__ e3, uint64_t n, unsigned long long* __restrict__ keys,
+                                uint32_t* __restrict__ codes) {
+  for (uint64_t p = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; p < n; p += uint64_t(gridDim.x) * blockDim.x) {
+    keys[p] = pl_third_of(e3, uint32_t(p));
+    codes[p] = uint32_t(p);
   }
+}
+
+__global__ void k_pl_pair_keys(const uint32_t* __restrict__ e3, const uint32_t* __restrict__ codes, uint64_t n,
+                               unsigned long long* __restrict__ keys) {
+  for (uint64_t p = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; p < n; p += uint64_t(gridDim.x) * blockDim.x) {
+    const uint32_t code = codes[p];
+    const uint64_t i = code / 3;
+    const uint32_t s = code % 3;
+    const unsigned long long a = e3[3 * i], b = e3[3 * i + 1], c = e3[3 * i + 2];
+    keys[p] = s == 0 ? ((a << 32) | b) : (s == 1 ? ((a << 32) | c) : ((b << 32) | c));
+  }
+}
+
+// One-hot of adjacency class cl over the entries (for the prefix counts).
+__global__ void k_pl_class_flags(const uint8_t* __restrict__ adj, uint64_t n, uint32_t cl, uint32_t* __restrict__ out) {
+  for (uint64_t p = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; p < n; p += uint64_t(gridDim.x) * blockDim.x)
+    out[p] = adj[p] == cl ? 1u : 0u;
 }
 
 // Hash index over the runs of the sorted pair keys.  First pass: every run's
@@ -495,16 +543,17 @@ __global__ void k_pl_index_counts(const unsigned long long* __restrict__ keys, u
   }
 }
 
-// Per pair entry: the third node of its 3-node hyperedge and that node's
-// pairwise adjacency to the two nodes of the key.
+// Per pair entry: its 3-node hyperedge (the code, in place), the third node
+// and that node's pairwise adjacency to the two nodes of the key.
 __global__ void k_pl_third(const uint32_t* __restrict__ e3, const unsigned long long* __restrict__ keys,
-                           const uint32_t* __restrict__ edge, uint64_t n, Set64 hs2, uint32_t* __restrict__ third,
+                           uint32_t* __restrict__ edge, uint64_t n, Set64 hs2, uint32_t* __restrict__ third,
                            uint8_t* __restrict__ adj) {
   for (uint64_t p = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; p < n; p += uint64_t(gridDim.x) * blockDim.x) {
     const unsigned long long key = keys[p];
     const uint32_t x = uint32_t(key >> 32), y = uint32_t(key);
-    const uint32_t* f = e3 + 3ull * edge[p];
-    const uint32_t t = f[0] ^ f[1] ^ f[2] ^ x ^ y;
+    const uint32_t code = edge[p];
+    const uint32_t t = pl_third_of(e3, code);
+    edge[p] = code / 3;
     third[p] = t;
     adj[p] = uint8_t(uint32_t(has2(hs2, x, t)) | (uint32_t(has2(hs2, y, t)) << 1));
   }
@@ -718,7 +767,71 @@ int ensure_edge_stats(hm_graph* H, hipStream_t st) {
   return HM_OK;
 }
 
-// The pair -> 3-node hyperedge index of H, built on first use.
+// Every 3-node subset of every 4-node hyperedge, packed as in quad_find, with
+// the hyperedge's fourth node.
+__global__ void k_quad_keys(const uint32_t* __restrict__ e4, uint64_t n4, int q, unsigned long long* __restrict__ keys,
+                            uint32_t* __restrict__ fourth) {
+  for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n4; i += uint64_t(gridDim.x) * blockDim.x) {
+    const unsigned long long m[4] = {e4[4 * i], e4[4 * i + 1], e4[4 * i + 2], e4[4 * i + 3]};
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const unsigned long long x = m[s == 0 ? 1 : 0], y = m[s <= 1 ? 2 : 1], z = m[s <= 2 ? 3 : 2];
+      keys[4 * i + s] = (x << (2 * q)) | (y << q) | z;
+      fourth[4 * i + s] = uint32_t(m[s]);
+    }
+  }
+}
+
+// The 3-node subset -> 4-node hyperedge index (H->q_*), when the packed key
+// fits 63 bits; otherwise none (q_bits = 0) and the incidence lists serve.
+int build_quad_index(hm_graph* H, hipStream_t st) {
+  const uint64_t n4 = H->n_by_size[4];
+  int bits = 1;
+  while (bits < 32 && (1ull << bits) < H->n_nodes) ++bits;
+  if (n4 == 0 || 3 * bits > 63) return HM_OK;
+  const uint64_t n = 4 * n4;
+  void *k = nullptr, *f = nullptr, *kt = nullptr, *ft = nullptr, *slots = nullptr;
+  int rc = dalloc(&k, n * sizeof(unsigned long long));
+  if (rc == HM_OK) rc = dalloc(&f, n * sizeof(uint32_t));
+  if (rc == HM_OK) rc = dalloc(&kt, n * sizeof(unsigned long long));
+  if (rc == HM_OK) rc = dalloc(&ft, n * sizeof(uint32_t));
+  if (rc == HM_OK) {
+    k_quad_keys<<<grid_cap(n4, 256, 4096), 256, 0, st>>>(H->e4, n4, bits, static_cast<unsigned long long*>(k),
+                                                         static_cast<uint32_t*>(f));
+    if (hipGetLastError() != hipSuccess) rc = HM_EDEVICE;
+  }
+  if (rc == HM_OK)
+    rc = radix_sort_pairs(static_cast<unsigned long long*>(k), static_cast<uint32_t*>(f),
+                          static_cast<unsigned long long*>(kt), static_cast<uint32_t*>(ft), n, 3 * bits, st);
+  const unsigned long long cap = pow2_capacity(n);
+  if (rc == HM_OK) rc = dalloc(&slots, 2 * cap * sizeof(unsigned long long));
+  if (rc == HM_OK) rc = fill_u64(static_cast<unsigned long long*>(slots), kEmpty64, 2 * cap, st);
+  if (rc == HM_OK) {
+    const unsigned g = grid_cap(n, 256, 4096);
+    k_pl_index_starts<<<g, 256, 0, st>>>(static_cast<const unsigned long long*>(k), n,
+                                         static_cast<unsigned long long*>(slots), cap - 1);
+    k_pl_index_counts<<<g, 256, 0, st>>>(static_cast<const unsigned long long*>(k), n,
+                                         static_cast<unsigned long long*>(slots), cap - 1);
+    if (hipGetLastError() != hipSuccess) rc = HM_EDEVICE;
+  }
+  if (rc == HM_OK && hipStreamSynchronize(st) != hipSuccess) rc = HM_EDEVICE;
+  dfree(k);
+  dfree(kt);
+  dfree(ft);
+  if (rc != HM_OK) {
+    dfree(f);
+    dfree(slots);
+    return rc;
+  }
+  H->q_slot = static_cast<unsigned long long*>(slots);
+  H->q_mask = cap - 1;
+  H->q_fourth = static_cast<uint32_t*>(f);
+  H->q_bits = bits;
+  return HM_OK;
+}
+
+// The pair -> 3-node hyperedge index of H, built on first use (with the
+// 4-node index beside it).
 int ensure_pair_links(hm_graph* H, hipStream_t st) {
   note_use(H, st);
   if (H->pl_keys || H->n_by_size[3] == 0) return HM_OK;
@@ -728,23 +841,32 @@ int ensure_pair_links(hm_graph* H, hipStream_t st) {
   int rc = dalloc(&e, n * sizeof(uint32_t));
   if (rc == HM_OK) rc = dalloc(&kt, n * sizeof(unsigned long long));
   if (rc == HM_OK) rc = dalloc(&et, n * sizeof(uint32_t));
-  if (rc == HM_OK) {
-    k_pair_link_keys<<<grid_cap(H->n_by_size[3], 256, 4096), 256, 0, st>>>(
-        H->e3, H->n_by_size[3], static_cast<unsigned long long*>(k), static_cast<uint32_t*>(e));
-    if (hipGetLastError() != hipSuccess) rc = HM_EDEVICE;
-  }
   int bits = 1;
   while (bits < 32 && (1ull << bits) < H->n_nodes) ++bits;
+  if (rc == HM_OK) {
+    k_pl_third_keys<<<grid_cap(n, 256, 4096), 256, 0, st>>>(H->e3, n, static_cast<unsigned long long*>(k),
+                                                            static_cast<uint32_t*>(e));
+    if (hipGetLastError() != hipSuccess) rc = HM_EDEVICE;
+  }
+  if (rc == HM_OK)
+    rc = radix_sort_pairs(static_cast<unsigned long long*>(k), static_cast<uint32_t*>(e),
+                          static_cast<unsigned long long*>(kt), static_cast<uint32_t*>(et), n, bits, st);
+  if (rc == HM_OK) {
+    k_pl_pair_keys<<<grid_cap(n, 256, 4096), 256, 0, st>>>(H->e3, static_cast<const uint32_t*>(e), n,
+                                                           static_cast<unsigned long long*>(k));
+    if (hipGetLastError() != hipSuccess) rc = HM_EDEVICE;
+  }
   if (rc == HM_OK)
     rc = radix_sort_pairs(static_cast<unsigned long long*>(k), static_cast<uint32_t*>(e),
                           static_cast<unsigned long long*>(kt), static_cast<uint32_t*>(et), n, 32 + bits, st);
   // the index: at most n distinct keys, load at most 1/2
   const unsigned long long cap = pow2_capacity(n);
-  void *slots = nullptr, *codeg = nullptr, *third = nullptr, *adj = nullptr;
+  void *slots = nullptr, *codeg = nullptr, *third = nullptr, *adj = nullptr, *pre = nullptr;
   if (rc == HM_OK) rc = dalloc(&slots, 2 * cap * sizeof(unsigned long long));
   if (rc == HM_OK) rc = dalloc(&codeg, cap * sizeof(uint32_t));
   if (rc == HM_OK) rc = dalloc(&third, n * sizeof(uint32_t));
   if (rc == HM_OK) rc = dalloc(&adj, n * sizeof(uint8_t));
+  if (rc == HM_OK) rc = dalloc(&pre, 4 * (n + 1) * sizeof(uint32_t));
   if (rc == HM_OK) rc = fill_u64(static_cast<unsigned long long*>(slots), kEmpty64, 2 * cap, st);
   if (rc == HM_OK) {
     const unsigned g = grid_cap(n, 256, 4096);
@@ -752,12 +874,20 @@ int ensure_pair_links(hm_graph* H, hipStream_t st) {
                                          static_cast<unsigned long long*>(slots), cap - 1);
     k_pl_index_counts<<<g, 256, 0, st>>>(static_cast<const unsigned long long*>(k), n,
                                          static_cast<unsigned long long*>(slots), cap - 1);
-    k_pl_third<<<g, 256, 0, st>>>(H->e3, static_cast<const unsigned long long*>(k), static_cast<const uint32_t*>(e), n,
+    k_pl_third<<<g, 256, 0, st>>>(H->e3, static_cast<const unsigned long long*>(k), static_cast<uint32_t*>(e), n,
                                   H->hs2, static_cast<uint32_t*>(third), static_cast<uint8_t*>(adj));
     k_pl_codeg<<<grid_cap((n + kWave - 1) / kWave, kWavesPerBlock, 4096), kThreads, 0, st>>>(
         view_of(H), static_cast<const unsigned long long*>(k), n, static_cast<const unsigned long long*>(slots),
         cap - 1, static_cast<uint32_t*>(codeg));
     if (hipGetLastError() != hipSuccess) rc = HM_EDEVICE;
+  }
+  // prefix counts of the entries by adjacency class (the flags reuse et)
+  for (uint32_t cl = 0; cl < 4 && rc == HM_OK; ++cl) {
+    uint32_t* out = static_cast<uint32_t*>(pre) + cl * (n + 1);
+    k_pl_class_flags<<<grid_cap(n, 256, 4096), 256, 0, st>>>(static_cast<const uint8_t*>(adj), n, cl,
+                                                             static_cast<uint32_t*>(et));
+    if (hipGetLastError() != hipSuccess) rc = HM_EDEVICE;
+    if (rc == HM_OK) rc = scan_exclusive_u32(static_cast<const uint32_t*>(et), out, n, out + n, st);
   }
   if (rc == HM_OK && hipStreamSynchronize(st) != hipSuccess) rc = HM_EDEVICE;
   dfree(kt);
@@ -769,6 +899,7 @@ int ensure_pair_links(hm_graph* H, hipStream_t st) {
     dfree(codeg);
     dfree(third);
     dfree(adj);
+    dfree(pre);
     return rc;
   }
   H->pl_keys = static_cast<unsigned long long*>(k);
@@ -778,7 +909,8 @@ int ensure_pair_links(hm_graph* H, hipStream_t st) {
   H->pl_codeg = static_cast<uint32_t*>(codeg);
   H->pl_third = static_cast<uint32_t*>(third);
   H->pl_adj = static_cast<uint8_t*>(adj);
-  return HM_OK;
+  H->pl_pre = static_cast<uint32_t*>(pre);
+  return build_quad_index(H, st);
 }
 
 PairLinks pair_links_of(const hm_graph* H) {
@@ -791,6 +923,11 @@ PairLinks pair_links_of(const hm_graph* H) {
   pl.codeg = H->pl_codeg;
   pl.third = H->pl_third;
   pl.adj = H->pl_adj;
+  pl.pre = H->pl_pre;
+  pl.q_slot = reinterpret_cast<const ulonglong2*>(H->q_slot);
+  pl.q_mask = H->q_mask;
+  pl.q_fourth = H->q_fourth;
+  pl.q_bits = H->q_bits;
   pl.hub_rank = H->hub_rank;
   pl.hub_bits = H->hub_bits;
   pl.hub_w = H->hub_words;
@@ -1012,8 +1149,18 @@ int count_sparse(const hm_graph* H, int k, hipStream_t st) {
     // no more workgroups than are resident at once: each wavefront's share is
     // fixed, and a workgroup that starts late would finish late
     const unsigned grid = grid_cap(n3, kWavesPerBlock, resident_blocks(reinterpret_cast<const void*>(k_sp_b4)));
-    ProfileScope ps("k_sp_b4", st);
-    k_sp_b4<<<grid, kThreads, 0, st>>>(v, pair_links_of(H), n3, H->b4_order, lut4, H->hist);
+    {
+      ProfileScope ps("k_sp_b4", st);
+      k_sp_b4<<<grid, kThreads, 0, st>>>(v, pair_links_of(H), n3, H->b4_order, lut4, H->hist);
+    }
+    HM_HIP(hipGetLastError());
+    const uint64_t n_entries = 3 * n3;
+    const unsigned grid_r =
+        grid_cap(n_entries, kWavesPerBlock, resident_blocks(reinterpret_cast<const void*>(k_sp_b4_runs)));
+    {
+      ProfileScope ps("k_sp_b4_runs", st);
+      k_sp_b4_runs<<<grid_r, kThreads, 0, st>>>(v, pair_links_of(H), lut4, H->hist);
+    }
     HM_HIP(hipGetLastError());
   }
   k_sp_shapes<<<1, 64, 0, st>>>(acc, k, cls, H->hist);

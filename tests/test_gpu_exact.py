@@ -187,13 +187,17 @@ def test_facetoface_order4_relabelled(hm):
     assert np.array_equal(_gpu_counts(hm, hp, 4), _golden("facetoface_N400_E30000", 4))
 
 
+@pytest.mark.parametrize("n_ids", [200_000, 1 << 22], ids=["ids_2e5", "ids_4M"])
 @pytest.mark.parametrize("seed", range(3))
-def test_large_node_ids(hm, seed):
-    """More nodes than the adjacency bit rows allow: pairs are probed in the hash set."""
+def test_large_node_ids(hm, seed, n_ids):
+    """More nodes than the adjacency bit rows allow: pairs are probed in the hash set.
+    At 2^22 ids three node ids no longer pack into 63 bits, so the 4-node
+    hyperedges holding a 3-node one are found through the incidence lists
+    instead of the 3-subset index."""
     base = W.random_small(2000 + seed, 60, 500, {2: 0.6, 3: 0.3, 4: 0.1})
     rng = np.random.default_rng(seed)
-    ids = np.sort(rng.choice(200_000, size=60, replace=False))
-    h = W.Hypergraph(200_000, ids[base.members.astype(np.int64)].astype(np.uint32), base.offsets.copy())
+    ids = np.sort(rng.choice(n_ids, size=60, replace=False))
+    h = W.Hypergraph(n_ids, ids[base.members.astype(np.int64)].astype(np.uint32), base.offsets.copy())
     for k in (3, 4):
         assert np.array_equal(_gpu_counts(hm, h, k), core.count_exact(h, k)), (seed, k)
 
