@@ -151,45 +151,82 @@ struct B4Ctx {
   uint64_t lo0, lo1, lo2, lo3, len0, len1, len2, len3, total;
 };
 
+__device__ __forceinline__ uint64_t readlane_u64(uint64_t x, int lane) {
+  return (uint64_t(uint32_t(__builtin_amdgcn_readlane(int(uint32_t(x >> 32)), lane))) << 32) |
+         uint32_t(__builtin_amdgcn_readlane(int(uint32_t(x)), lane));
+}
+
+// Every lane of the wavefront calls this.  The ten lookups e needs are spread
+// over lanes 0..9, which run the same probe loop each on its own table, so
+// that they take one round of memory latency rather than ten in a row; the
+// results are then read from those lanes.  Lanes 0..2: the pair index runs of
+// {a,b}, {a,c}, {b,c}; 3..5: the pairs' membership in the pair set; 6: the
+// run of e in the 4-node index; 7..9: the dense rows of a, b, c.
 __device__ __forceinline__ B4Ctx b4_ctx(const View& v, const PairLinks& pl, uint32_t a, uint32_t b, uint32_t c) {
+  const int lane = threadIdx.x & (kWave - 1);
   B4Ctx x;
   x.a = a;
   x.b = b;
   x.c = c;
-  x.base_p = has2(v.hs2, a, b) | (has2(v.hs2, a, c) << 1) | (has2(v.hs2, b, c) << 2) | (1u << 3);
-  const unsigned long long kab = ((unsigned long long)a << 32) | b, kac = ((unsigned long long)a << 32) | c,
-                           kbc = ((unsigned long long)b << 32) | c;
-  uint32_t l0, l1, l2;
-  pl_find(pl, kab, &x.lo0, &l0);
-  pl_find(pl, kac, &x.lo1, &l1);
-  pl_find(pl, kbc, &x.lo2, &l2);
-  x.len0 = l0;
-  x.len1 = l1;
-  x.len2 = l2;
+  const unsigned long long* base = nullptr;
+  unsigned long long key = 0, mask = 0;
+  uint32_t stride = 2;   // 64-bit words per slot: key, then value
+  if (lane < 3 && pl.n) {
+    const uint32_t u = lane == 2 ? b : a, w = lane == 0 ? b : c;
+    key = ((unsigned long long)u << 32) | w;
+    base = reinterpret_cast<const unsigned long long*>(pl.slot);
+    mask = pl.mask;
+  } else if (lane >= 3 && lane < 6) {
+    const uint32_t u = lane == 5 ? b : a, w = lane == 3 ? b : c;
+    key = key2(u, w);
+    base = v.hs2.slot;
+    mask = v.hs2.mask;
+    stride = 1;
+  } else if (lane == 6 && pl.q_bits) {
+    const int q = pl.q_bits;
+    key = ((unsigned long long)a << (2 * q)) | ((unsigned long long)b << q) | c;
+    base = reinterpret_cast<const unsigned long long*>(pl.q_slot);
+    mask = pl.q_mask;
+  }
+  unsigned long long val = 0;
+  if (base) {
+    unsigned long long h = mix64(key) & mask;
+    while (true) {
+      const unsigned long long k = base[stride * h];
+      if (k == key) {
+        val = stride == 2 ? base[2 * h + 1] : 1ull;
+        break;
+      }
+      if (k == kEmpty64) break;
+      h = (h + 1) & mask;
+    }
+  } else if (lane >= 7 && lane < 10) {
+    val = uint32_t(hub_of(pl, lane == 7 ? a : (lane == 8 ? b : c)));
+  }
+  // the same in every lane: kept in scalar registers
+  const uint64_t r0 = readlane_u64(val, 0), r1 = readlane_u64(val, 1), r2 = readlane_u64(val, 2);
+  x.lo0 = r0 >> 32;
+  x.len0 = uint32_t(r0);
+  x.lo1 = r1 >> 32;
+  x.len1 = uint32_t(r1);
+  x.lo2 = r2 >> 32;
+  x.len2 = uint32_t(r2);
+  x.base_p = uint32_t(__builtin_amdgcn_readlane(int(val), 3)) | (uint32_t(__builtin_amdgcn_readlane(int(val), 4)) << 1) |
+             (uint32_t(__builtin_amdgcn_readlane(int(val), 5)) << 2) | (1u << 3);
+  x.ra = __builtin_amdgcn_readlane(int(val), 7);
+  x.rb = __builtin_amdgcn_readlane(int(val), 8);
+  x.rc = __builtin_amdgcn_readlane(int(val), 9);
   if (pl.q_bits) {
-    uint32_t l3;
-    quad_find(pl, a, b, c, &x.lo3, &l3);
-    x.len3 = l3;
+    const uint64_t r6 = readlane_u64(val, 6);
+    x.lo3 = r6 >> 32;
+    x.len3 = uint32_t(r6);
   } else {
     const uint32_t fa = v.i4_off[a + 1] - v.i4_off[a], fb = v.i4_off[b + 1] - v.i4_off[b],
                    fc = v.i4_off[c + 1] - v.i4_off[c];
     const uint32_t m4 = (fa <= fb && fa <= fc) ? a : (fb <= fc ? b : c);
-    x.lo3 = v.i4_off[m4];
-    x.len3 = v.i4_off[m4 + 1] - x.lo3;
+    x.lo3 = uniform_u64(v.i4_off[m4]);
+    x.len3 = uniform_u64(v.i4_off[m4 + 1] - v.i4_off[m4]);
   }
-  x.ra = int(uniform_u32(uint32_t(hub_of(pl, a))));
-  x.rb = int(uniform_u32(uint32_t(hub_of(pl, b))));
-  x.rc = int(uniform_u32(uint32_t(hub_of(pl, c))));
-  // the same in every lane: kept in scalar registers
-  x.base_p = uniform_u32(x.base_p);
-  x.lo0 = uniform_u64(x.lo0);
-  x.lo1 = uniform_u64(x.lo1);
-  x.lo2 = uniform_u64(x.lo2);
-  x.lo3 = uniform_u64(x.lo3);
-  x.len0 = uniform_u64(x.len0);
-  x.len1 = uniform_u64(x.len1);
-  x.len2 = uniform_u64(x.len2);
-  x.len3 = uniform_u64(x.len3);
   x.total = x.len0 + x.len1 + x.len2 + x.len3;
   return x;
 }
@@ -341,6 +378,52 @@ __device__ __forceinline__ B4Short b4_short(const View& v, const PairLinks& pl, 
   return s;
 }
 
+// Membership probes of b4_exception_node: with SEQ each test runs to its end
+// where it starts, so that only its result stays live (fewer registers, for
+// kernels where most tests are list comparisons); without, the first slot
+// is loaded at the start and the tests of one node resolve together.
+template <bool SEQ>
+struct P128 {
+  Probe128 p;
+};
+template <>
+struct P128<true> {
+  bool r;
+};
+template <bool SEQ>
+struct P64 {
+  Probe64 p;
+};
+template <>
+struct P64<true> {
+  bool r;
+};
+template <bool SEQ>
+__device__ __forceinline__ P128<SEQ> p128_start(const Set128& s, Key128 k) {
+  if constexpr (SEQ) return P128<true>{set128_has(s, k)};
+  else return P128<false>{probe128_start(s, k)};
+}
+template <bool SEQ>
+__device__ __forceinline__ P128<SEQ> p3_start(const Set128& s, uint32_t a, uint32_t b, uint32_t c) {
+  sort3(a, b, c);
+  return p128_start<SEQ>(s, key3(a, b, c));
+}
+template <bool SEQ>
+__device__ __forceinline__ bool p128_end(const Set128& s, const P128<SEQ>& q) {
+  if constexpr (SEQ) return q.r;
+  else return probe128_end(s, q.p);
+}
+template <bool SEQ>
+__device__ __forceinline__ P64<SEQ> p2_start(const Set64& s, uint32_t u, uint32_t w) {
+  if constexpr (SEQ) return P64<true>{has2(s, u, w)};
+  else return P64<false>{probe2_start(s, u, w)};
+}
+template <bool SEQ>
+__device__ __forceinline__ bool p64_end(const Set64& s, const P64<SEQ>& q) {
+  if constexpr (SEQ) return q.r;
+  else return probe64_end(s, q.p);
+}
+
 // The exceptional node at flat position t of the ranges of x, each node
 // once (by the first hyperedge that makes it exceptional).  Returns 0 when the
 // position holds none; else bit 4 set, its pairwise combination in bits 0..2,
@@ -352,7 +435,7 @@ __device__ __forceinline__ B4Short b4_short(const View& v, const PairLinks& pl, 
 // node of a 3-node hyperedge on pair {a,b}, {a,c} or {b,c} of e, pair_adj its
 // pairwise adjacency to that pair's lower and higher node in bits 0 and 1;
 // 3: the fourth node of a 4-node hyperedge holding e, pair_adj unused).
-template <bool OWN>
+template <bool OWN, bool SEQ = false>
 __device__ __forceinline__ uint32_t b4_exception_node(const View& v, const PairLinks& pl, const B4Ctx& x, int slot,
                                                       uint32_t y, uint32_t pair_adj, uint32_t* pat,
                                                       const B4Short& sh) {
@@ -370,20 +453,20 @@ __device__ __forceinline__ uint32_t b4_exception_node(const View& v, const PairL
     // and its pair with m, for its pairwise combination.
     const uint32_t m = slot == 0 ? c : (slot == 1 ? b : a);
     if (OWN && y < m) {
-      Probe128 qab, qac;
-      if (slot >= 1 && !hab) qab = probe3_start(v.hs3, a, b, y);
-      if (slot == 2 && !hac) qac = probe3_start(v.hs3, a, c, y);
+      P128<SEQ> qab, qac;
+      if (slot >= 1 && !hab) qab = p3_start<SEQ>(v.hs3, a, b, y);
+      if (slot == 2 && !hac) qac = p3_start<SEQ>(v.hs3, a, c, y);
       // m's neighbours, when held: c's for slot 0, b's for slot 1, a's for slot 2
       const bool hm = slot == 0 ? hc : (slot == 1 ? hb : ha);
       const int rm = slot == 0 ? rc : (slot == 1 ? rb : ra);
-      Probe64 pm;
-      if (!hm && rm < 0) pm = probe2_start(v.hs2, m, y);
-      if (slot >= 1 && (hab ? in_short(sh.mem, sh.n_ab, y) : probe128_end(v.hs3, qab))) return 0;
-      if (slot == 2 && (hac ? in_short(sh.mem + kB4ShortRun, sh.n_ac, y) : probe128_end(v.hs3, qac))) return 0;
+      P64<SEQ> pm;
+      if (!hm && rm < 0) pm = p2_start<SEQ>(v.hs2, m, y);
+      if (slot >= 1 && (hab ? in_short(sh.mem, sh.n_ab, y) : p128_end<SEQ>(v.hs3, qab))) return 0;
+      if (slot == 2 && (hac ? in_short(sh.mem + kB4ShortRun, sh.n_ac, y) : p128_end<SEQ>(v.hs3, qac))) return 0;
       const uint32_t mv =
           hm ? uint32_t(in_short(sh.mem + kB4AdjAt + (2 - uint32_t(slot)) * kB4ShortAdj,
                                  slot == 0 ? sh.n_c : (slot == 1 ? sh.n_b : sh.n_a), y))
-             : (rm >= 0 ? hub_adj(pl, rm, y) : uint32_t(probe64_end(v.hs2, pm)));
+             : (rm >= 0 ? hub_adj(pl, rm, y) : uint32_t(p64_end<SEQ>(v.hs2, pm)));
       const uint32_t lo = pair_adj & 1u, hi = pair_adj >> 1;
       const uint32_t av = slot == 2 ? mv : lo;
       const uint32_t bv = slot == 0 ? hi : (slot == 1 ? mv : lo);
@@ -394,50 +477,50 @@ __device__ __forceinline__ uint32_t b4_exception_node(const View& v, const PairL
   // Every membership test the set e u {y} needs, issued together: the
   // 3-node sets through y not already known from the slot, the 4-node set
   // (unless the slot is the 4-node hyperedges'), y's pairs with a, b, c.
-  Probe128 pab, pac, pbc, pq;
-  if (slot != 0 && !hab) pab = probe3_start(v.hs3, a, b, y);
-  if (slot != 1 && !hac) pac = probe3_start(v.hs3, a, c, y);
-  if (slot != 2 && !hbc) pbc = probe3_start(v.hs3, b, c, y);
+  P128<SEQ> pab, pac, pbc, pq;
+  if (slot != 0 && !hab) pab = p3_start<SEQ>(v.hs3, a, b, y);
+  if (slot != 1 && !hac) pac = p3_start<SEQ>(v.hs3, a, c, y);
+  if (slot != 2 && !hbc) pbc = p3_start<SEQ>(v.hs3, b, c, y);
   if (slot < 3 && !hq) {
     uint32_t s0 = a, s1 = b, s2 = c, s3 = y;
     // ascending 4-tuple for the 4-node probe
     if (s3 < s2) { const uint32_t tt = s2; s2 = s3; s3 = tt; }
     if (s2 < s1) { const uint32_t tt = s1; s1 = s2; s2 = tt; }
     if (s1 < s0) { const uint32_t tt = s0; s0 = s1; s1 = tt; }
-    pq = probe128_start(v.hs4, key4(s0, s1, s2, s3));
+    pq = p128_start<SEQ>(v.hs4, key4(s0, s1, s2, s3));
   }
   // y's pairs with the two members of the slot's pair come with the entry
-  Probe64 pa, pb, pc;
-  if ((slot == 2 || slot == 3) && !ha && ra < 0) pa = probe2_start(v.hs2, a, y);
-  if ((slot == 1 || slot == 3) && !hb && rb < 0) pb = probe2_start(v.hs2, b, y);
-  if ((slot == 0 || slot == 3) && !hc && rc < 0) pc = probe2_start(v.hs2, c, y);
+  P64<SEQ> pa, pb, pc;
+  if ((slot == 2 || slot == 3) && !ha && ra < 0) pa = p2_start<SEQ>(v.hs2, a, y);
+  if ((slot == 1 || slot == 3) && !hb && rb < 0) pb = p2_start<SEQ>(v.hs2, b, y);
+  if ((slot == 0 || slot == 3) && !hc && rc < 0) pc = p2_start<SEQ>(v.hs2, c, y);
   const uint32_t abv =
-      slot == 0 ? 1u : uint32_t(hab ? in_short(sh.mem, sh.n_ab, y) : probe128_end(v.hs3, pab));
+      slot == 0 ? 1u : uint32_t(hab ? in_short(sh.mem, sh.n_ab, y) : p128_end<SEQ>(v.hs3, pab));
   const uint32_t acv =
-      slot == 1 ? 1u : uint32_t(hac ? in_short(sh.mem + kB4ShortRun, sh.n_ac, y) : probe128_end(v.hs3, pac));
+      slot == 1 ? 1u : uint32_t(hac ? in_short(sh.mem + kB4ShortRun, sh.n_ac, y) : p128_end<SEQ>(v.hs3, pac));
   const uint32_t bcv =
-      slot == 2 ? 1u : uint32_t(hbc ? in_short(sh.mem + 2 * kB4ShortRun, sh.n_bc, y) : probe128_end(v.hs3, pbc));
+      slot == 2 ? 1u : uint32_t(hbc ? in_short(sh.mem + 2 * kB4ShortRun, sh.n_bc, y) : p128_end<SEQ>(v.hs3, pbc));
   // each exceptional node once: a 3-node hyperedge of an earlier slot takes it
   if (slot == 1 && abv) return 0;
   if (slot == 2 && (abv || acv)) return 0;
   if (slot == 3 && (abv || acv || bcv)) return 0;
   const uint32_t quad =
-      slot == 3 ? 1u : uint32_t(hq ? in_short(sh.mem + kB4QAt, sh.n_q, y) : probe128_end(v.hs4, pq));
+      slot == 3 ? 1u : uint32_t(hq ? in_short(sh.mem + kB4QAt, sh.n_q, y) : p128_end<SEQ>(v.hs4, pq));
   const uint32_t av =
       slot == 0 || slot == 1
           ? (pair_adj & 1u)
           : (ha ? uint32_t(in_short(sh.mem + kB4AdjAt, sh.n_a, y))
-                : (ra >= 0 ? hub_adj(pl, ra, y) : uint32_t(probe64_end(v.hs2, pa))));
+                : (ra >= 0 ? hub_adj(pl, ra, y) : uint32_t(p64_end<SEQ>(v.hs2, pa))));
   const uint32_t bv =
       slot == 0 ? (pair_adj >> 1)
                 : (slot == 2 ? (pair_adj & 1u)
                              : (hb ? uint32_t(in_short(sh.mem + kB4AdjAt + kB4ShortAdj, sh.n_b, y))
-                                   : (rb >= 0 ? hub_adj(pl, rb, y) : uint32_t(probe64_end(v.hs2, pb)))));
+                                   : (rb >= 0 ? hub_adj(pl, rb, y) : uint32_t(p64_end<SEQ>(v.hs2, pb)))));
   const uint32_t cv =
       slot == 1 || slot == 2
           ? (pair_adj >> 1)
           : (hc ? uint32_t(in_short(sh.mem + kB4AdjAt + 2 * kB4ShortAdj, sh.n_c, y))
-                : (rc >= 0 ? hub_adj(pl, rc, y) : uint32_t(probe64_end(v.hs2, pc))));
+                : (rc >= 0 ? hub_adj(pl, rc, y) : uint32_t(p64_end<SEQ>(v.hs2, pc))));
   const uint32_t combo = av | (bv << 1) | (cv << 2);
   bool counted = !quad;   // a 4-node hyperedge: counted on its own, or larger than a sampled 3-node one
   if (OWN && counted) {
@@ -453,23 +536,23 @@ __device__ __forceinline__ uint32_t b4_exception_node(const View& v, const PairL
   return 16u | (counted ? 8u : 0u) | combo;
 }
 
-template <bool OWN>
+template <bool OWN, bool SEQ = false>
 __device__ __forceinline__ uint32_t b4_exception(const View& v, const PairLinks& pl, const B4Ctx& x, uint64_t t,
                                                  uint32_t* pat, const B4Short& sh) {
   // slot and offset of t, with constant indices only (registers)
   if (t < x.len0) {
     const uint64_t p = x.lo0 + t;
-    return b4_exception_node<OWN>(v, pl, x, 0, pl.third[p], pl.adj[p], pat, sh);
+    return b4_exception_node<OWN, SEQ>(v, pl, x, 0, pl.third[p], pl.adj[p], pat, sh);
   }
   if (t < x.len0 + x.len1) {
     const uint64_t p = x.lo1 + (t - x.len0);
-    return b4_exception_node<OWN>(v, pl, x, 1, pl.third[p], pl.adj[p], pat, sh);
+    return b4_exception_node<OWN, SEQ>(v, pl, x, 1, pl.third[p], pl.adj[p], pat, sh);
   }
   if (t < x.len0 + x.len1 + x.len2) {
     const uint64_t p = x.lo2 + (t - x.len0 - x.len1);
-    return b4_exception_node<OWN>(v, pl, x, 2, pl.third[p], pl.adj[p], pat, sh);
+    return b4_exception_node<OWN, SEQ>(v, pl, x, 2, pl.third[p], pl.adj[p], pat, sh);
   }
-  if (pl.q_bits) return b4_exception_node<OWN>(v, pl, x, 3, pl.q_fourth[x.lo3 + (t - x.len0 - x.len1 - x.len2)], 0u,
+  if (pl.q_bits) return b4_exception_node<OWN, SEQ>(v, pl, x, 3, pl.q_fourth[x.lo3 + (t - x.len0 - x.len1 - x.len2)], 0u,
                                               pat, sh);
   const uint32_t* f = v.e4 + 4ull * v.i4_idx[x.lo3 + (t - x.len0 - x.len1 - x.len2)];
   const uint32_t f0 = f[0], f1 = f[1], f2 = f[2], f3 = f[3];
@@ -477,7 +560,7 @@ __device__ __forceinline__ uint32_t b4_exception(const View& v, const PairLinks&
   const uint32_t hit = uint32_t(f0 == a || f0 == b || f0 == c) + uint32_t(f1 == a || f1 == b || f1 == c) +
                        uint32_t(f2 == a || f2 == b || f2 == c) + uint32_t(f3 == a || f3 == b || f3 == c);
   if (hit != 3) return 0;
-  return b4_exception_node<OWN>(v, pl, x, 3, f0 ^ f1 ^ f2 ^ f3 ^ a ^ b ^ c, 0u, pat, sh);
+  return b4_exception_node<OWN, SEQ>(v, pl, x, 3, f0 ^ f1 ^ f2 ^ f3 ^ a ^ b ^ c, 0u, pat, sh);
 }
 
 // The combination pattern of e u {v} for a non-exceptional v.
@@ -487,7 +570,7 @@ __device__ inline uint32_t b4_combo_pattern(const B4Ctx& x, uint32_t cmb) {
 
 // Exact counting (OWN = true) and the bit-free sampler's inline path: one
 // wavefront per hyperedge.
-template <bool OWN>
+template <bool OWN, bool SEQ = false>
 __device__ void b4_sparse(const View& v, const PairLinks& pl, uint32_t a, uint32_t b, uint32_t c, const uint8_t* lut,
                           unsigned long long* h_main, unsigned long long* h_sub, uint32_t* short_mem = nullptr,
                           bool runs = true) {
@@ -504,7 +587,7 @@ __device__ void b4_sparse(const View& v, const PairLinks& pl, uint32_t a, uint32
   const uint64_t t0 = runs ? 0 : x.len0 + x.len1 + x.len2;
   for (uint64_t t = t0 + lane; t < x.total; t += kWave) {
     uint32_t pat;
-    const uint32_t r = b4_exception<OWN>(v, pl, x, t, &pat, sh);
+    const uint32_t r = b4_exception<OWN, SEQ>(v, pl, x, t, &pat, sh);
     if (!r) continue;
     const uint32_t combo = r & 7u;
     dn1 += combo == 1;
@@ -581,7 +664,7 @@ __device__ inline uint64_t run_find(const PairLinks& pl, uint64_t lo, uint32_t l
 // as the exception walk does; when the run is not longer than those lists,
 // the run itself is walked instead.
 __device__ void b4_run_entry(const View& v, const PairLinks& pl, uint64_t p, const uint8_t* lut,
-                             unsigned long long* h_main, unsigned long long* h_sub) {
+                             unsigned long long* h_main, unsigned long long* h_sub, uint32_t* short_mem) {
   const int lane = threadIdx.x & (kWave - 1);
   const unsigned long long key = pl.keys[p];
   const bool alone = (p == 0 || pl.keys[p - 1] != key) && (p + 1 == pl.n || pl.keys[p + 1] != key);
@@ -589,44 +672,29 @@ __device__ void b4_run_entry(const View& v, const PairLinks& pl, uint64_t p, con
   const uint32_t px = uint32_t(key >> 32), py = uint32_t(key), t = pl.third[p];
   const int slot = t > py ? 0 : (t > px ? 1 : 2);
   const uint32_t a = slot == 2 ? t : px, b = slot == 0 ? py : (slot == 1 ? t : px), c = slot == 0 ? t : py;
-  // the run of the pair
-  uint64_t lo;
-  uint32_t L;
-  pl_find(pl, key, &lo, &L);
-  lo = uniform_u64(lo);
-  L = uniform_u32(L);
   const uint32_t t_off = uniform_u32(v.g2_off[t]), dt = uniform_u32(v.g2_off[t + 1]) - t_off;
-  // A run no longer than t's pairwise row is walked whatever the other lists
-  // hold: e's pattern and the members' dense rows are all that walk needs.
-  // Otherwise the runs of {x, t} and {y, t} and the 4-node lists decide.
-  B4Ctx x;
-  bool walk_run = uint64_t(L) - 1 <= dt;
-  uint64_t lo_xt = 0, lo_yt = 0;
-  uint32_t len_xt = 0, len_yt = 0;
-  uint64_t listed = dt;
-  if (walk_run) {
-    x.a = a;
-    x.b = b;
-    x.c = c;
-    const uint32_t pp = has2(v.hs2, px, py), cl = pl.adj[p], l = cl & 1u, h = cl >> 1;
-    x.base_p = uniform_u32((slot == 0 ? (pp | (l << 1) | (h << 2)) : (slot == 1 ? (l | (pp << 1) | (h << 2))
-                                                                                 : (l | (h << 1) | (pp << 2)))) |
-                           (1u << 3));
-    x.ra = int(uniform_u32(uint32_t(hub_of(pl, a))));
-    x.rb = int(uniform_u32(uint32_t(hub_of(pl, b))));
-    x.rc = int(uniform_u32(uint32_t(hub_of(pl, c))));
-    x.lo0 = x.lo1 = x.lo2 = x.lo3 = x.len0 = x.len1 = x.len2 = x.len3 = x.total = 0;
-  } else {
-    x = b4_ctx(v, pl, a, b, c);
-    lo_xt = slot == 0 ? x.lo1 : x.lo0;
-    len_xt = uint32_t(slot == 0 ? x.len1 : x.len0);
-    lo_yt = slot == 2 ? x.lo1 : x.lo2;
-    len_yt = uint32_t(slot == 2 ? x.len1 : x.len2);
-    listed = uint64_t(dt) + len_xt + len_yt + x.len3;
-    walk_run = uint64_t(L) - 1 <= listed;
-  }
+  const B4Ctx x = b4_ctx(v, pl, a, b, c);
+  // the run of the pair
+  const uint64_t lo = slot == 0 ? x.lo0 : (slot == 1 ? x.lo1 : x.lo2);
+  const uint32_t L = uint32_t(slot == 0 ? x.len0 : (slot == 1 ? x.len1 : x.len2));
+  // the runs of {x, t} and {y, t}
+  const uint64_t lo_xt = slot == 0 ? x.lo1 : x.lo0;
+  const uint32_t len_xt = uint32_t(slot == 0 ? x.len1 : x.len0);
+  const uint64_t lo_yt = slot == 2 ? x.lo1 : x.lo2;
+  const uint32_t len_yt = uint32_t(slot == 2 ? x.len1 : x.len2);
+  const uint64_t listed = uint64_t(dt) + len_xt + len_yt + x.len3;
+  const bool walk_run = uint64_t(L) - 1 <= listed;
   const int rt = slot == 0 ? x.rc : (slot == 1 ? x.rb : x.ra);   // t's dense row, or -1
-  const B4Short sh = b4_short_none();
+  // the short lists of e in LDS (runs and rows of at most 64 entries, the
+  // 4-node hyperedges holding e): membership tests become comparisons
+  const B4Short sh = b4_short(v, pl, x, short_mem);
+  const bool ht = (slot == 0 ? sh.n_c : (slot == 1 ? sh.n_b : sh.n_a)) != kB4NotHeld;
+  const uint32_t* t_row = sh.mem + kB4AdjAt + (slot == 0 ? 2u : (slot == 1 ? 1u : 0u)) * kB4ShortAdj;
+  // runs of {x, t} and {y, t} among e's three pair runs: slot 0 holds them at
+  // ac, bc; slot 1 at ab, bc; slot 2 at ab, ac
+  const uint32_t n_xt = slot == 0 ? sh.n_ac : sh.n_ab, n_yt = slot == 2 ? sh.n_ac : sh.n_bc;
+  const uint32_t* xt_list = sh.mem + (slot == 0 ? kB4ShortRun : 0u);
+  const uint32_t* yt_list = sh.mem + (slot == 2 ? kB4ShortRun : 2 * kB4ShortRun);
   uint32_t dn1 = 0, dn2 = 0, dn3 = 0, dn4 = 0, dn5 = 0, dn6 = 0, dn7 = 0;
   uint32_t ml0 = 0, ml1 = 0, ml2 = 0, ml3 = 0, mg0 = 0, mg1 = 0, mg2 = 0, mg3 = 0;
   const uint64_t n_items = walk_run ? L : listed;
@@ -661,16 +729,19 @@ __device__ void b4_run_entry(const View& v, const PairLinks& pl, uint64_t p, con
       }
       if (z == px || z == py || z == t) continue;
       // each related node once, from the first list holding it
-      if (src >= 1 && (rt >= 0 ? hub_adj(pl, rt, z) : uint32_t(has2(v.hs2, t, z)))) continue;
+      if (src >= 1 &&
+          (ht ? in_short(t_row, slot == 0 ? sh.n_c : (slot == 1 ? sh.n_b : sh.n_a), z)
+              : (rt >= 0 ? hub_adj(pl, rt, z) : uint32_t(has2(v.hs2, t, z)))))
+        continue;
       if (src >= 2) {
         uint32_t s0 = px, s1 = t, s2 = z;
         sort3(s0, s1, s2);
-        if (set128_has(v.hs3, key3(s0, s1, s2))) continue;
+        if (n_xt != kB4NotHeld ? in_short(xt_list, n_xt, z) : set128_has(v.hs3, key3(s0, s1, s2))) continue;
       }
       if (src >= 3) {
         uint32_t s0 = py, s1 = t, s2 = z;
         sort3(s0, s1, s2);
-        if (set128_has(v.hs3, key3(s0, s1, s2))) continue;
+        if (n_yt != kB4NotHeld ? in_short(yt_list, n_yt, z) : set128_has(v.hs3, key3(s0, s1, s2))) continue;
       }
       const uint64_t j = run_find(pl, lo, L, z);
       if (j == ~0ull) continue;   // {x, y, z} is not a 3-node hyperedge
@@ -686,7 +757,7 @@ __device__ void b4_run_entry(const View& v, const PairLinks& pl, uint64_t p, con
       mg3 += !below && cls == 3;
     }
     uint32_t pat;
-    const uint32_t r = b4_exception_node<true>(v, pl, x, slot, z, cls, &pat, sh);
+    const uint32_t r = b4_exception_node<true, true>(v, pl, x, slot, z, cls, &pat, sh);
     if (!r) continue;
     const uint32_t combo = r & 7u;
     dn1 += combo == 1;

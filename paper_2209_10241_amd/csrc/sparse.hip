@@ -399,7 +399,7 @@ __global__ void __launch_bounds__(kThreads) k_sp_b4(View v, PairLinks pl, uint64
   uint32_t* short_mem = short_lists[threadIdx.x / kWave];
   for (uint64_t j = wave; j < n3; j += n_waves) {
     const uint64_t i = order[j];
-    b4_sparse<true>(v, pl, v.e3[3 * i], v.e3[3 * i + 1], v.e3[3 * i + 2], lut, h_main, h_sub, short_mem, false);
+    b4_sparse<true, true>(v, pl, v.e3[3 * i], v.e3[3 * i + 1], v.e3[3 * i + 2], lut, h_main, h_sub, short_mem, false);
   }
   __syncthreads();
   unsigned long long* hc = hist_copy(hist, kExactHistStride);
@@ -410,17 +410,20 @@ __global__ void __launch_bounds__(kThreads) k_sp_b4(View v, PairLinks pl, uint64
 // (b) at order 4 without bit rows, the pair-run terms: one wavefront per
 // entry of the pair index, in index order, so that the entries of one run
 // (and their shared lists) are taken by neighbouring wavefronts.
-__global__ void __launch_bounds__(kThreads) k_sp_b4_runs(View v, PairLinks pl, const uint8_t* __restrict__ lut_g,
+// (four wavefronts per SIMD: its items are chains of dependent lookups)
+__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 8))) k_sp_b4_runs(View v, PairLinks pl, const uint8_t* __restrict__ lut_g,
                                                          unsigned long long* __restrict__ hist) {
   __shared__ uint8_t lut[2048];
   __shared__ unsigned long long h_main[256], h_sub[256];
+  __shared__ __align__(16) uint32_t short_lists[kWavesPerBlock][kB4ShortWords];
   load_lut(lut, lut_g, 2048);
   h_main[threadIdx.x] = 0;
   h_sub[threadIdx.x] = 0;
   __syncthreads();
   const uint64_t wave = uint64_t(blockIdx.x) * kWavesPerBlock + threadIdx.x / kWave;
   const uint64_t n_waves = uint64_t(gridDim.x) * kWavesPerBlock;
-  for (uint64_t p = wave; p < pl.n; p += n_waves) b4_run_entry(v, pl, p, lut, h_main, h_sub);
+  uint32_t* short_mem = short_lists[threadIdx.x / kWave];
+  for (uint64_t p = wave; p < pl.n; p += n_waves) b4_run_entry(v, pl, p, lut, h_main, h_sub, short_mem);
   __syncthreads();
   unsigned long long* hc = hist_copy(hist, kExactHistStride);
   flush(h_main, hc + kMain, 256);
