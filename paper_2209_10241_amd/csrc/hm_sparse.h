@@ -328,20 +328,26 @@ __device__ __forceinline__ bool in_short(const uint32_t* l, uint32_t n, uint32_t
 }
 
 // Every lane of the wavefront calls this; mem is the wavefront's LDS.
-__device__ __forceinline__ B4Short b4_short(const View& v, const PairLinks& pl, const B4Ctx& x, uint32_t* mem) {
+// `want` selects the lists to hold (the others are probed): bits 0..2 the
+// runs of {a,b}, {a,c}, {b,c}; 3..5 the rows of a, b, c; 6 the 4-node list.
+constexpr uint32_t kB4WantAll = 0x7F;
+__device__ __forceinline__ B4Short b4_short(const View& v, const PairLinks& pl, const B4Ctx& x, uint32_t* mem,
+                                            uint32_t want = kB4WantAll) {
   const uint32_t lane = threadIdx.x & (kWave - 1);
   const unsigned long long below = (1ull << lane) - 1ull;
   B4Short s;
   s.mem = mem;
-  s.n_ab = x.len0 <= kB4ShortRun ? uint32_t(x.len0) : kB4NotHeld;
-  s.n_ac = x.len1 <= kB4ShortRun ? uint32_t(x.len1) : kB4NotHeld;
-  s.n_bc = x.len2 <= kB4ShortRun ? uint32_t(x.len2) : kB4NotHeld;
+  s.n_ab = (want & 1u) && x.len0 <= kB4ShortRun ? uint32_t(x.len0) : kB4NotHeld;
+  s.n_ac = (want & 2u) && x.len1 <= kB4ShortRun ? uint32_t(x.len1) : kB4NotHeld;
+  s.n_bc = (want & 4u) && x.len2 <= kB4ShortRun ? uint32_t(x.len2) : kB4NotHeld;
   if (lane < kB4ShortRun) {
     if (s.n_ab != kB4NotHeld) mem[lane] = lane < x.len0 ? pl.third[x.lo0 + lane] : kNoNode;
     if (s.n_ac != kB4NotHeld) mem[kB4ShortRun + lane] = lane < x.len1 ? pl.third[x.lo1 + lane] : kNoNode;
     if (s.n_bc != kB4NotHeld) mem[2 * kB4ShortRun + lane] = lane < x.len2 ? pl.third[x.lo2 + lane] : kNoNode;
   }
-  const uint32_t da = deg2_of(v, x.a), db = deg2_of(v, x.b), dc = deg2_of(v, x.c);
+  const uint32_t da = (want & 8u) ? uniform_u32(deg2_of(v, x.a)) : kB4NotHeld;
+  const uint32_t db = (want & 16u) ? uniform_u32(deg2_of(v, x.b)) : kB4NotHeld;
+  const uint32_t dc = (want & 32u) ? uniform_u32(deg2_of(v, x.c)) : kB4NotHeld;
   s.n_a = da <= kB4ShortAdj ? da : kB4NotHeld;
   s.n_b = db <= kB4ShortAdj ? db : kB4NotHeld;
   s.n_c = dc <= kB4ShortAdj ? dc : kB4NotHeld;
@@ -351,7 +357,7 @@ __device__ __forceinline__ B4Short b4_short(const View& v, const PairLinks& pl, 
     if (s.n_c != kB4NotHeld) mem[kB4AdjAt + 2 * kB4ShortAdj + lane] = lane < dc ? v.g2_adj[v.g2_off[x.c] + lane] : kNoNode;
   }
   s.n_q = kB4NotHeld;
-  if (x.len3 <= kWave) {
+  if ((want & 64u) && x.len3 <= kWave) {
     bool hold = false;
     uint32_t y = 0;
     if (lane < x.len3 && pl.q_bits) {
@@ -685,9 +691,12 @@ __device__ void b4_run_entry(const View& v, const PairLinks& pl, uint64_t p, con
   const uint64_t listed = uint64_t(dt) + len_xt + len_yt + x.len3;
   const bool walk_run = uint64_t(L) - 1 <= listed;
   const int rt = slot == 0 ? x.rc : (slot == 1 ? x.rb : x.ra);   // t's dense row, or -1
-  // the short lists of e in LDS (runs and rows of at most 64 entries, the
-  // 4-node hyperedges holding e): membership tests become comparisons
-  const B4Short sh = b4_short(v, pl, x, short_mem);
+  // the short lists this pass tests against, in LDS (at most 64 entries; the
+  // 4-node hyperedges holding e): the runs of {x, t} and {y, t}, t's row;
+  // membership tests against them are comparisons.  (The pair's own run and
+  // the rows of x and y are never tested: the entries carry them.)
+  const uint32_t want = (slot == 0 ? (2u | 4u | 32u) : (slot == 1 ? (1u | 4u | 16u) : (1u | 2u | 8u))) | 64u;
+  const B4Short sh = b4_short(v, pl, x, short_mem, want);
   const bool ht = (slot == 0 ? sh.n_c : (slot == 1 ? sh.n_b : sh.n_a)) != kB4NotHeld;
   const uint32_t* t_row = sh.mem + kB4AdjAt + (slot == 0 ? 2u : (slot == 1 ? 1u : 0u)) * kB4ShortAdj;
   // runs of {x, t} and {y, t} among e's three pair runs: slot 0 holds them at
@@ -781,6 +790,8 @@ __device__ void b4_run_entry(const View& v, const PairLinks& pl, uint64_t p, con
   dn[5] = wave_sum_u32(dn5);
   dn[6] = wave_sum_u32(dn6);
   dn[7] = wave_sum_u32(dn7);
+  // walking the lists: the related entries by class below and above t,
+  // whose complement the prefix counts give
   uint32_t ml[4] = {0, 0, 0, 0}, mg[4] = {0, 0, 0, 0};
   if (!walk_run) {
     ml[0] = wave_sum_u32(ml0);
