@@ -28,18 +28,6 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_exact_k4_facetoface_N
 # hardware counters is only reported while these are unchanged
 EXACT_SOURCES = ("exact.hip", "hm_items.h", "hm_b4.h", "hm_device.h", "hm_internal.h")
 HBM_PEAK_GBS = 8000.0
-# a hash probe into a table larger than the caches is one 64-byte transaction
-PROBE_BYTES = 64
-# longest list of a 3-node hyperedge's neighbourhood that its fill-in step
-# holds in LDS and compares against instead of probing
-SHORT_RUN = 64
-SHORT_Q = 16
-# longest pairwise row of a member of that hyperedge it holds in LDS
-SHORT_ADJ = 64
-# nodes with at least this many pairwise neighbours keep a dense adjacency
-# row, highest degrees first, within HUB_ROW_BYTES
-HUB_MIN_DEGREE = 256
-HUB_ROW_BYTES = 32 << 20
 # integer VALU issue rate: 256 CUs x 64 lanes per cycle x 2.4 GHz
 ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 
@@ -78,98 +66,51 @@ def _unit_counts(e2: np.ndarray, e3: np.ndarray, n_nodes: int, words: int) -> di
             "id_c4_pair_word_tasks": n * (n - 1) // 2 * words}
 
 
-def _b4_lookup_model(e2: np.ndarray, e3: np.ndarray, e4: np.ndarray, n_nodes: int,
-                     hub_min_degree: int = HUB_MIN_DEGREE) -> dict:
-    """Memory transactions of the 3-node-hyperedge fill-in step without bit
-    rows (one wavefront per 3-node hyperedge e = {a<b<c}), counted from the
-    strata.  Per e: 3 pair probes for e's own pattern, 3 pair-index lookups
-    and 1 codegree lookup; 2 pair probes per entry of the shortest pairwise
-    row among a, b, c.  Membership in the 3-node hyperedges through a pair
-    of e is a comparison when that pair's run has at most SHORT_RUN entries
-    (held in LDS), else a probe; membership in the 4-node hyperedges holding
-    e likewise when the 4-node incidence list read has at most 64 entries
-    and at most SHORT_Q of them hold e.  Per other 3-node hyperedge
-    {y} u P on a pair P of e, with m the member of e outside P: when y > m,
-    the two other 3-node memberships, the 4-node membership and the pair
-    {m, y}; else the pair {m, y} and the 3-node memberships of the pairs
-    before P.  Per 4-node hyperedge holding e: its three 3-node memberships
-    and three pairs.  A pair with a member of e whose pairwise row has at
-    most SHORT_ADJ entries (held in LDS) is a comparison; with a member that
-    has a dense adjacency row (at least hub_min_degree neighbours, highest
-    degrees first within HUB_ROW_BYTES) it is one streamed 4-byte word.
-    Streamed bytes: 4 per row entry, 5 per pair-index entry (third node and
-    its adjacency), 20 per entry of the 4-node incidence list read, 60 for e
-    and its row bounds, the short lists and rows read once more into LDS,
-    and the dense-row words."""
+def _b4_positions(e2: np.ndarray, e3: np.ndarray, e4: np.ndarray, n_nodes: int) -> dict:
+    """Work of the 3-node-hyperedge step without bit rows, counted from the
+    strata as its two kernels walk it.  k_sp_b4, per 3-node hyperedge
+    e = {a<b<c}: the shortest pairwise row among a, b, c (each entry tested
+    against the other two members) and the 4-node hyperedges holding e.
+    k_sp_b4_runs, per entry of the pair index (a pair P of e with the third
+    node t) whose run holds L >= 2 entries: the other L - 1 entries of the
+    run when L - 1 <= d(t) + L(P0, t) + L(P1, t) + (4-node hyperedges holding
+    e), else those lists.  Each position is a few lookups (a third node, a
+    membership test against a list in LDS, a dense-row word or a hash probe)."""
     n = np.int64(n_nodes)
     if len(e3) == 0:
-        return {"probes": 0, "stream_bytes": 0, "hyperedges": 0, "entries": 0}
+        return {"positions_b4": 0, "positions_runs": 0, "hyperedges": 0, "entries": 0, "entries_active": 0}
     deg2 = np.bincount(e2.reshape(-1).astype(np.int64), minlength=n_nodes) if len(e2) else np.zeros(n_nodes, np.int64)
     t = e3.astype(np.int64)
     a, b, c = t[:, 0], t[:, 1], t[:, 2]
     dmin = np.minimum(np.minimum(deg2[a], deg2[b]), deg2[c])
-    # nodes with a dense adjacency row
-    hub = np.zeros(n_nodes, dtype=bool)
-    if hub_min_degree > 0:
-        cand = np.nonzero(deg2 >= hub_min_degree)[0]
-        cand = cand[np.lexsort((cand, -deg2[cand]))]
-        hub[cand[: HUB_ROW_BYTES // (4 * ((n_nodes + 31) // 32))]] = True
-    # 3-node hyperedges on each pair (ab, ac, bc), and how many of their
-    # third nodes lie below the member of e outside the pair
-    pk = np.concatenate([a * n + b, a * n + c, b * n + c])
-    third = np.concatenate([c, b, a])
-    uk, inv, cnt = np.unique(pk, return_inverse=True, return_counts=True)
-    L = cnt[inv].reshape(3, -1)
-    by_third = np.sort(pk * n + third)
-    below = (np.searchsorted(by_third, pk * n + third) - np.searchsorted(by_third, pk * n)).reshape(3, -1)
-    late = L - 1 - below
-    probed = (L > SHORT_RUN).astype(np.int64)   # membership through that pair is a probe
-    # 4-node hyperedges per node, and those holding each e
     if len(e4):
         q = e4.astype(np.int64)
-        deg4 = np.bincount(q.reshape(-1), minlength=n_nodes)
         sub = np.concatenate([(q[:, i] * n + q[:, j]) * n + q[:, k]
                               for i, j, k in ((0, 1, 2), (0, 1, 3), (0, 2, 3), (1, 2, 3))])
-        k3 = (a * n + b) * n + c
         su, sc = np.unique(sub, return_counts=True)
+        k3 = (a * n + b) * n + c
         pos = np.minimum(np.searchsorted(su, k3), len(su) - 1)
         holding = np.where(su[pos] == k3, sc[pos], 0)
     else:
-        deg4 = np.zeros(n_nodes, np.int64)
         holding = np.zeros(len(t), np.int64)
-    fa, fb, fc = deg4[a], deg4[b], deg4[c]
-    len3 = np.where((fa <= fb) & (fa <= fc), fa, np.where(fb <= fc, fb, fc))
-    q_held = (len3 <= 64) & (holding <= SHORT_Q)
-    qp = (~q_held).astype(np.int64)
-    ab, ac, bc = probed
-    # pairs with a member of e are comparisons when its pairwise row is held,
-    # dense-row words when it has one, probes otherwise
-    da, db, dc = deg2[a], deg2[b], deg2[c]
-    ha, hb, hc = hub[a].astype(np.int64), hub[b].astype(np.int64), hub[c].astype(np.int64)
-    pa, pb, pc = ((d > SHORT_ADJ).astype(np.int64) * (1 - h) for d, h in ((da, ha), (db, hb), (dc, hc)))
-    # the shortest row is walked against the other two members
-    r_a = (da <= db) & (da <= dc)
-    r_b = ~r_a & (db <= dc)
-    x_hub = np.where(r_a, hb, ha)              # first other member: b when a is walked, else a
-    y_hub = np.where(r_a | r_b, hc, hb)        # second: c unless c is walked
-    walk_probes = dmin * ((1 - x_hub) + (1 - y_hub))
-    walk_words = dmin * (x_hub + y_hub)
-    # (a held row takes precedence over a dense one)
-    wa, wb, wc = (h * (d > SHORT_ADJ).astype(np.int64) for d, h in ((da, ha), (db, hb), (dc, hc)))
-    pair_words = (late[0] + below[0]) * wc + (late[1] + below[1]) * wb + (late[2] + below[2]) * wa \
-        + holding * (wa + wb + wc)
-    probes = (7 + walk_probes
-              + late[0] * (ac + bc + qp + pc) + late[1] * (ab + bc + qp + pb) + late[2] * (ab + ac + qp + pa)
-              + below[0] * pc + below[1] * (ab + pb) + below[2] * (ab + ac + pa)
-              + holding * (ab + ac + bc + pa + pb + pc)).sum()
-    held_rows = sum(np.where(d <= SHORT_ADJ, d, 0) for d in (da, db, dc))
-    stream = (4 * dmin + 5 * L.sum(axis=0) + 20 * len3 + 60
-              + 4 * (L * (1 - probed)).sum(axis=0) + 20 * np.where(len3 <= 64, len3, 0) + 4 * held_rows
-              + 4 * (walk_words + pair_words)).sum()
-    # positions the exception loops walk: every entry of the three pair runs
-    # and of the 4-node incidence list read
-    entries = int(L.sum() + len3.sum())
-    return {"probes": int(probes), "stream_bytes": int(stream), "hyperedges": int(len(t)), "entries": entries}
+    pk = np.concatenate([a * n + b, a * n + c, b * n + c])
+    uk, cnt = np.unique(pk, return_counts=True)
+
+    def run_len(x, y):
+        k = np.minimum(x, y) * n + np.maximum(x, y)
+        i = np.minimum(np.searchsorted(uk, k), len(uk) - 1)
+        return np.where(uk[i] == k, cnt[i], 0)
+
+    runs = 0
+    active = 0
+    for p0, p1, th in ((a, b, c), (a, c, b), (b, c, a)):
+        L = run_len(p0, p1)
+        listed = deg2[th] + run_len(p0, th) + run_len(p1, th) + holding
+        on = L >= 2
+        active += int(on.sum())
+        runs += int(np.where(on, np.where(L - 1 <= listed, L - 1, listed), 0).sum())
+    return {"positions_b4": int((dmin + holding).sum()), "positions_runs": runs, "hyperedges": int(len(t)),
+            "entries": 3 * int(len(t)), "entries_active": active}
 
 
 def exact_source_digest() -> str:
@@ -195,6 +136,38 @@ def measured_traffic() -> dict:
         cols = [c.strip() for c in l.strip().strip("|").split("|")]
         if len(cols) == 6 and cols[0].startswith("k_") and cols[5].replace(".", "").isdigit():
             out[cols[0].split("<")[0]] = float(cols[5])
+    return out
+
+
+LOOKUP_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_lookup_k_sp_b4_heavy_tailed.md")
+LOOKUP_SOURCES = ("sparse.hip", "hm_sparse.h", "hm_device.h", "hm_internal.h", "prims.hip")
+
+
+def lookup_source_digest() -> str:
+    import hashlib
+    d = hashlib.sha256()
+    for name in LOOKUP_SOURCES:
+        with open(os.path.join(ROOT, "paper_2209_10241_amd", "csrc", name), "rb") as f:
+            d.update(f.read())
+    return d.hexdigest()[:16]
+
+
+def measured_lookup_traffic() -> dict:
+    """HBM bytes per count of k_sp_b4 plus k_sp_b4_runs (FETCH_SIZE + WRITE_SIZE,
+    copy-calibrated) by workload, if the profile is still current."""
+    try:
+        lines = open(LOOKUP_TRAFFIC_FILE).read().splitlines()
+    except OSError:
+        return {}
+    digest = next((l.split("`")[1] for l in lines if l.startswith("source digest:")), None)
+    if digest != lookup_source_digest():
+        return {}
+    out = {}
+    for l in lines:
+        cols = [c.strip() for c in l.strip().strip("|").split("|")]
+        if len(cols) == 4 and cols[0] in ("coauthorship_N1e6_E2e6", "communication_N5e4_E5e6") \
+                and cols[3].replace(".", "").isdigit():
+            out[cols[0]] = float(cols[3])
     return out
 
 
@@ -252,14 +225,22 @@ def large_workloads(hm, W, torch, seeds: int = 32, exact_only: bool = False) -> 
         prof = hm.hm_profile_read()
         hm.hm_profile_enable(False)
         kernels = {k: {"launches": n, "avg_ms": ms / max(n, 1)} for k, (n, ms) in prof.items()}
-        model = _b4_lookup_model(g.export(2), g.export(3), g.export(4), h.n_nodes)
+        model = _b4_positions(g.export(2), g.export(3), g.export(4), h.n_nodes)
         lookup = None
-        if "k_sp_b4" in kernels:
-            nbytes = model["probes"] * PROBE_BYTES + model["stream_bytes"]
-            gbs = nbytes / (kernels["k_sp_b4"]["avg_ms"] / 1e3) / 1e9
-            lookup = {"kernel": "k_sp_b4", "bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                      "frac": gbs / HBM_PEAK_GBS, "bytes_per_launch": nbytes, "probe_bytes": PROBE_BYTES,
-                      "entries_per_s": model["entries"] / (kernels["k_sp_b4"]["avg_ms"] / 1e3), **model}
+        if "k_sp_b4" in kernels and "k_sp_b4_runs" in kernels:
+            ms = kernels["k_sp_b4"]["avg_ms"] + kernels["k_sp_b4_runs"]["avg_ms"]
+            lookup = {"kernels": ["k_sp_b4", "k_sp_b4_runs"], "ms": ms,
+                      "positions_per_s": (model["positions_b4"] + model["positions_runs"]) / (ms / 1e3), **model}
+            # HBM bytes of the two kernels from the committed counter runs
+            # (FETCH_SIZE + WRITE_SIZE per launch), while the sources match
+            meas = measured_lookup_traffic().get(name)
+            if meas:
+                gbs = meas / (ms / 1e3) / 1e9
+                lookup.update({"bound": "latency", "traffic": meas, "achieved": gbs, "peak": HBM_PEAK_GBS,
+                               "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS})
+            else:
+                lookup.update({"bound": "latency", "traffic": None, "achieved": None, "peak": HBM_PEAK_GBS,
+                               "unit": "GB/s", "frac": None})
         if exact_only:
             out[name] = {"n_nodes": h.n_nodes, "unique_by_size": [st["n2"], st["n3"], st["n4"], st["n5plus"]],
                          "connected_4_sets": int(exact.sum()), "ingest_ms": ingest_ms, "exact_ms": exact_ms,
