@@ -125,33 +125,53 @@ __global__ void __launch_bounds__(kSortThreads) k_sort_hist(const unsigned long 
   hist[uint64_t(threadIdx.x) * nb + blockIdx.x] = counts[threadIdx.x];
 }
 
-// Stable scatter: items of a tile are taken round by round (position order is
-// round-major, then thread), ranks inside a wavefront come from ballots over
-// the digit bits, ranks across wavefronts from per-round LDS counts.
+// Stable scatter in two steps.  First the tile is sorted by digit in LDS:
+// items are taken round by round (position order is round-major, then
+// thread), ranks inside a wavefront come from ballots over the digit bits and
+// ranks across wavefronts from per-round LDS counts, on top of the tile's own
+// digit offsets (the exclusive scan of its counts from k_sort_hist).  Then
+// thread t writes the tile's t-th item in digit order to its digit's global
+// range, so that each digit's items of the tile go out as one contiguous run.
 __global__ void __launch_bounds__(kSortThreads) k_sort_scatter(
     const unsigned long long* __restrict__ keys, const uint32_t* __restrict__ vals,
     unsigned long long* __restrict__ out_keys, uint32_t* __restrict__ out_vals, uint64_t n, int shift,
-    int digit_bits, const uint32_t* __restrict__ offsets, uint32_t nb) {
-  __shared__ uint32_t running[256];
+    int digit_bits, const uint32_t* __restrict__ hist, const uint32_t* __restrict__ offsets, uint32_t nb) {
+  __shared__ unsigned long long s_keys[kSortTile];
+  __shared__ uint32_t s_vals[kSortTile];
+  __shared__ uint32_t tile_off[256], global_off[256], running[256];
   __shared__ uint32_t wave_cnt[kSortWaves][256];
+  __shared__ uint32_t wave_sums[kSortWaves];
   const uint32_t digit_mask = (1u << digit_bits) - 1u;
-  running[threadIdx.x] = offsets[uint64_t(threadIdx.x) * nb + blockIdx.x];
+  {
+    const uint32_t c = hist[uint64_t(threadIdx.x) * nb + blockIdx.x];
+    uint32_t total;
+    const uint32_t off = block_exclusive_scan(c, wave_sums, &total);
+    tile_off[threadIdx.x] = off;
+    running[threadIdx.x] = off;
+    global_off[threadIdx.x] = offsets[uint64_t(threadIdx.x) * nb + blockIdx.x];
+  }
   for (int w = 0; w < kSortWaves; ++w) wave_cnt[w][threadIdx.x] = 0;
   __syncthreads();
   const int lane = threadIdx.x & (kWave - 1);
   const int wave = threadIdx.x / kWave;
   const unsigned long long lt_mask = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
   const uint64_t base = uint64_t(blockIdx.x) * kSortTile;
+  // the tile's items, all loads issued before the first is needed
+  unsigned long long rk[kSortItems];
+  uint32_t rv[kSortItems];
+#pragma unroll
+  for (int r = 0; r < kSortItems; ++r) {
+    const uint64_t i = base + uint64_t(r) * kSortThreads + threadIdx.x;
+    rk[r] = i < n ? keys[i] : 0ull;
+    rv[r] = i < n ? vals[i] : 0u;
+  }
+#pragma unroll
   for (int r = 0; r < kSortItems; ++r) {
     const uint64_t i = base + uint64_t(r) * kSortThreads + threadIdx.x;
     const bool valid = i < n;
-    unsigned long long key = 0;
-    uint32_t val = 0, d = 0;
-    if (valid) {
-      key = keys[i];
-      val = vals[i];
-      d = uint32_t(key >> shift) & digit_mask;
-    }
+    const unsigned long long key = rk[r];
+    const uint32_t val = rv[r];
+    const uint32_t d = valid ? uint32_t(key >> shift) & digit_mask : 0u;
     unsigned long long peers = __ballot(valid);
     for (int b = 0; b < digit_bits; ++b) {
       const bool bit = (d >> b) & 1u;
@@ -164,8 +184,8 @@ __global__ void __launch_bounds__(kSortThreads) k_sort_scatter(
     if (valid) {
       uint32_t pos = running[d] + rank;
       for (int w = 0; w < wave; ++w) pos += wave_cnt[w][d];
-      out_keys[pos] = key;
-      out_vals[pos] = val;
+      s_keys[pos] = key;
+      s_vals[pos] = val;
     }
     __syncthreads();
     uint32_t add = 0;
@@ -175,6 +195,14 @@ __global__ void __launch_bounds__(kSortThreads) k_sort_scatter(
     }
     running[threadIdx.x] += add;
     __syncthreads();
+  }
+  const uint32_t tile_n = uint32_t(min<uint64_t>(uint64_t(kSortTile), n - base));
+  for (uint32_t j = threadIdx.x; j < tile_n; j += kSortThreads) {
+    const unsigned long long key = s_keys[j];
+    const uint32_t d = uint32_t(key >> shift) & digit_mask;
+    const uint32_t pos = global_off[d] + (j - tile_off[d]);
+    out_keys[pos] = key;
+    out_vals[pos] = s_vals[j];
   }
 }
 
@@ -265,7 +293,7 @@ int radix_sort_ws(unsigned long long* keys, uint32_t* vals, unsigned long long* 
     k_sort_hist<<<nb, kSortThreads, 0, st>>>(src_k, n, shift, (1u << db) - 1u, hist, nb);
     HM_HIP(hipGetLastError());
     HM_TRY(scan_u32_ws(hist, offs, uint64_t(256) * nb, nullptr, scan_ws, st));
-    k_sort_scatter<<<nb, kSortThreads, 0, st>>>(src_k, src_v, dst_k, dst_v, n, shift, db, offs, nb);
+    k_sort_scatter<<<nb, kSortThreads, 0, st>>>(src_k, src_v, dst_k, dst_v, n, shift, db, hist, offs, nb);
     HM_HIP(hipGetLastError());
     std::swap(src_k, dst_k);
     std::swap(src_v, dst_v);
@@ -338,7 +366,7 @@ int radix_sort_pairs(unsigned long long* keys, uint32_t* vals, unsigned long lon
                               nullptr, st);
     if (rc == HM_OK) {
       k_sort_scatter<<<nb, kSortThreads, 0, st>>>(src_k, src_v, dst_k, dst_v, n, shift, db,
-                                                  static_cast<uint32_t*>(offs), nb);
+                                                  static_cast<const uint32_t*>(hist), static_cast<uint32_t*>(offs), nb);
       if (hipGetLastError() != hipSuccess) rc = HM_EDEVICE;
     }
     std::swap(src_k, dst_k);
