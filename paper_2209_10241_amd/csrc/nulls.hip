@@ -48,20 +48,52 @@ namespace {
 
 constexpr int kMaxRepairRounds = 64;
 
-__global__ void k_null_keys(uint32_t c0, uint32_t R, uint64_t T, const unsigned long long* __restrict__ seed_p,
-                            unsigned long long* keys, uint32_t* vals) {
+// Sorting R copies' random orders at once: item i = c * per + x of copy c
+// carries the word w = word 0 of Philox at counter (x, round, 0, 0) under
+// key (seed, domain << 32 | c0 + c), and each copy's items are wanted in the
+// order of (w, x).  The sort key is (c << 32) | (w >> 32); k_fix_ties then
+// orders the rare runs of equal keys by (low half of w, i), which gives the
+// order of the full word with ties by position.
+__device__ inline unsigned long long order_word(uint64_t i, uint64_t per, uint64_t round, uint32_t c0,
+                                                unsigned long long domain, unsigned long long seed) {
+  return philox4x64_10(i % per, round, 0, 0, seed, (domain << 32) | (c0 + i / per)).v[0];
+}
+
+__global__ void k_order_keys(uint32_t c0, uint32_t R, uint64_t per, uint64_t round, unsigned long long domain,
+                             const unsigned long long* __restrict__ seed_p, unsigned long long* keys, uint32_t* vals) {
   const unsigned long long seed = *seed_p;
-  const uint64_t n = uint64_t(R) * T;
+  const uint64_t n = uint64_t(R) * per;
   for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += uint64_t(gridDim.x) * blockDim.x) {
-    const uint64_t c = i / T, t = i % T;
-    keys[i] = philox4x64_10(t, 0, 0, 0, seed, (kDomainNull << 32) | (c0 + c)).v[0];
+    const unsigned long long w = order_word(i, per, round, c0, domain, seed);
+    keys[i] = ((unsigned long long)(i / per) << 32) | (w >> 32);
     vals[i] = uint32_t(i);
   }
 }
 
-__global__ void k_copy_of(const uint32_t* __restrict__ vals, uint64_t n, uint64_t T, unsigned long long* keys) {
-  for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += uint64_t(gridDim.x) * blockDim.x)
-    keys[i] = vals[i] / T;
+__global__ void k_fix_ties(const unsigned long long* __restrict__ keys, uint32_t* __restrict__ vals, uint64_t n,
+                           uint64_t per, uint64_t round, uint32_t c0, unsigned long long domain,
+                           const unsigned long long* __restrict__ seed_p) {
+  const unsigned long long seed = *seed_p;
+  for (uint64_t p = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; p + 1 < n; p += uint64_t(gridDim.x) * blockDim.x) {
+    const unsigned long long k = keys[p];
+    if (keys[p + 1] != k || (p > 0 && keys[p - 1] == k)) continue;   // not the start of a run
+    uint64_t e = p + 2;
+    while (e < n && keys[e] == k) ++e;
+    // insertion sort of vals[p, e) by (low half of the word, value)
+    for (uint64_t i = p + 1; i < e; ++i) {
+      const uint32_t v = vals[i];
+      const uint32_t lo = uint32_t(order_word(v, per, round, c0, domain, seed));
+      uint64_t j = i;
+      while (j > p) {
+        const uint32_t u = vals[j - 1];
+        const uint32_t ulo = uint32_t(order_word(u, per, round, c0, domain, seed));
+        if (ulo < lo || (ulo == lo && u < v)) break;
+        vals[j] = u;
+        --j;
+      }
+      vals[j] = v;
+    }
+  }
 }
 
 __global__ void k_null_gather(const uint32_t* __restrict__ vals, uint64_t n, uint64_t T,
@@ -80,18 +112,6 @@ __global__ void k_cfg_init(uint32_t R, uint64_t T, const uint32_t* __restrict__ 
   const uint64_t n = uint64_t(R) * T;
   for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += uint64_t(gridDim.x) * blockDim.x)
     members[i] = src[i % T];
-}
-
-// round r's key of hyperedge i of copy c0 + c; vals = c * E + i
-__global__ void k_cfg_keys(uint32_t c0, uint32_t R, uint32_t E, uint32_t r, const unsigned long long* __restrict__ seed_p,
-                           unsigned long long* keys, uint32_t* vals) {
-  const unsigned long long seed = *seed_p;
-  const uint64_t n = uint64_t(R) * E;
-  for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += uint64_t(gridDim.x) * blockDim.x) {
-    const uint64_t c = i / E, e = i % E;
-    keys[i] = philox4x64_10(e, r, 0, 0, seed, (kDomainConfig << 32) | (c0 + c)).v[0];
-    vals[i] = uint32_t(i);
-  }
 }
 
 // One thread per (copy, pair): the pairwise reshuffle of the two hyperedges
@@ -294,15 +314,23 @@ __device__ inline uint32_t block_exclusive_scan(uint32_t v, uint32_t* wsum, uint
 }
 
 // Stable compaction of the indices i < n with flag(i) into out (ascending).
+// Each thread takes kCompactRun consecutive indices per round, so that one
+// workgroup scan serves kThreads * kCompactRun of them.
+constexpr uint32_t kCompactRun = 4;
 template <typename F>
 __device__ uint32_t block_compact(uint32_t n, F flag, uint32_t* out, uint32_t* wsum) {
   uint32_t count = 0;
-  for (uint32_t base = 0; base < n; base += kThreads) {
-    const uint32_t i = base + threadIdx.x;
-    const bool f = i < n && flag(i);
+  for (uint32_t base = 0; base < n; base += kThreads * kCompactRun) {
+    const uint32_t i0 = base + threadIdx.x * kCompactRun;
+    uint32_t bits = 0;
+#pragma unroll
+    for (uint32_t k = 0; k < kCompactRun; ++k)
+      if (i0 + k < n && flag(i0 + k)) bits |= 1u << k;
     uint32_t tot;
-    const uint32_t pos = block_exclusive_scan(f ? 1u : 0u, wsum, &tot);
-    if (f) out[count + pos] = i;
+    uint32_t pos = block_exclusive_scan(uint32_t(__popc(bits)), wsum, &tot);
+#pragma unroll
+    for (uint32_t k = 0; k < kCompactRun; ++k)
+      if (bits & (1u << k)) out[count + pos++] = i0 + k;
     count += tot;
   }
   __syncthreads();
@@ -310,8 +338,49 @@ __device__ uint32_t block_compact(uint32_t n, F flag, uint32_t* out, uint32_t* w
 }
 
 // Ascending bitonic sort of n_pad (a power of two) (key, aux) pairs in
-// device memory by one workgroup; ties are broken by aux.
-__device__ void block_bitonic(unsigned long long* key, uint32_t* aux, uint32_t* val, uint32_t n_pad) {
+// device memory by one workgroup; ties are broken by aux.  Up to
+// kLdsBitonic entries the sort runs on copies in LDS (lk, la, lv).
+constexpr uint32_t kLdsBitonic = 2048;
+__device__ void block_bitonic(unsigned long long* key, uint32_t* aux, uint32_t* val, uint32_t n_pad,
+                              unsigned long long* lk, uint32_t* la, uint32_t* lv) {
+  if (n_pad <= kLdsBitonic) {
+    for (uint32_t i = threadIdx.x; i < n_pad; i += kThreads) {
+      lk[i] = key[i];
+      la[i] = aux[i];
+      if (val) lv[i] = val[i];
+    }
+    __syncthreads();
+    for (uint32_t k = 2; k <= n_pad; k <<= 1)
+      for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+        for (uint32_t i = threadIdx.x; i < n_pad; i += kThreads) {
+          const uint32_t l = i ^ j;
+          if (l <= i) continue;
+          const bool asc = (i & k) == 0;
+          const bool greater = lk[i] > lk[l] || (lk[i] == lk[l] && la[i] > la[l]);
+          if (greater == asc) {
+            const unsigned long long tk = lk[i];
+            lk[i] = lk[l];
+            lk[l] = tk;
+            const uint32_t ta = la[i];
+            la[i] = la[l];
+            la[l] = ta;
+            if (val) {
+              const uint32_t tv = lv[i];
+              lv[i] = lv[l];
+              lv[l] = tv;
+            }
+          }
+        }
+        __syncthreads();
+      }
+    for (uint32_t i = threadIdx.x; i < n_pad; i += kThreads) {
+      key[i] = lk[i];
+      aux[i] = la[i];
+      if (val) val[i] = lv[i];
+    }
+    __syncthreads();
+    return;
+  }
   for (uint32_t k = 2; k <= n_pad; k <<= 1)
     for (uint32_t j = k >> 1; j > 0; j >>= 1) {
       for (uint32_t i = threadIdx.x; i < n_pad; i += kThreads) {
@@ -362,6 +431,8 @@ __global__ void __launch_bounds__(kThreads) k_null_repair(uint32_t c0, uint32_t 
                                                           const unsigned long long* __restrict__ seed_p,
                                                           RepairScratch sc, uint32_t* __restrict__ failed) {
   __shared__ uint32_t wsum[kWavesPerBlock];
+  __shared__ unsigned long long lk[kLdsBitonic];
+  __shared__ uint32_t la[kLdsBitonic], lv[kLdsBitonic];
   const unsigned long long seed = *seed_p;
   for (uint32_t c = blockIdx.x; c < R; c += gridDim.x) {
     uint32_t* m = members + uint64_t(c) * T;
@@ -392,7 +463,7 @@ __global__ void __launch_bounds__(kThreads) k_null_repair(uint32_t c0, uint32_t 
         aux[q] = 0;
       }
       __syncthreads();
-      block_bitonic(key, aux, nullptr, pad);
+      block_bitonic(key, aux, nullptr, pad, lk, la, lv);
       for (uint32_t q = threadIdx.x; q < pad; q += kThreads) chosen[q] = uint32_t(key[q]);
       __syncthreads();
       const uint32_t n_ch = block_compact(2 * n_bad, [&](uint32_t q) {
@@ -437,7 +508,7 @@ __global__ void __launch_bounds__(kThreads) k_null_repair(uint32_t c0, uint32_t 
         }
       }
       __syncthreads();
-      block_bitonic(key, aux, val, ppad);
+      block_bitonic(key, aux, val, ppad, lk, la, lv);
       // deal back and find the hyperedges that still repeat a node
       for (uint32_t q = threadIdx.x; q < n_ch; q += kThreads) {
         const unsigned long long b = off[chosen[q]];
@@ -1115,18 +1186,23 @@ int make_plan(const hm_graph* H, int k, uint32_t R, int model, int sweeps, NullP
   return HM_OK;
 }
 
+// P.svals := for each copy in turn, its `per` items in the order of their
+// words (see k_order_keys); no allocation, no sync.
+int enqueue_order(NullPlan& P, uint64_t n, uint64_t per, uint64_t round, unsigned long long domain, uint32_t c0,
+                  hipStream_t st) {
+  k_order_keys<<<grid_for(n), 256, 0, st>>>(c0, P.R, per, round, domain, P.seed, P.skeys, P.svals);
+  HM_HIP(hipGetLastError());
+  HM_TRY(radix_sort_ws(P.skeys, P.svals, P.skeys_tmp, P.svals_tmp, n, 32 + bits_for(P.R), P.sort_ws, st));
+  k_fix_ties<<<grid_for(n), 256, 0, st>>>(P.skeys, P.svals, n, per, round, c0, domain, P.seed);
+  HM_HIP(hipGetLastError());
+  return HM_OK;
+}
+
 // Stub matching of copies c0 .. c0+R-1 into P.members (no allocation, no sync).
 int enqueue_stubs(const hm_graph* H, NullPlan& P, uint32_t c0, hipStream_t st) {
   const uint64_t n = uint64_t(P.R) * P.T;
   if (n == 0) return HM_OK;
-  k_null_keys<<<grid_for(n), 256, 0, st>>>(c0, P.R, P.T, P.seed, P.skeys, P.svals);
-  HM_HIP(hipGetLastError());
-  HM_TRY(radix_sort_ws(P.skeys, P.svals, P.skeys_tmp, P.svals_tmp, n, 64, P.sort_ws, st));
-  if (P.R > 1) {
-    k_copy_of<<<grid_for(n), 256, 0, st>>>(P.svals, n, P.T, P.skeys);
-    HM_HIP(hipGetLastError());
-    HM_TRY(radix_sort_ws(P.skeys, P.svals, P.skeys_tmp, P.svals_tmp, n, bits_for(P.R), P.sort_ws, st));
-  }
+  HM_TRY(enqueue_order(P, n, P.T, 0, kDomainNull, c0, st));
   k_null_gather<<<grid_for(n), 256, 0, st>>>(P.svals, n, P.T, H->all_members, P.members);
   HM_HIP(hipGetLastError());
   HM_TRY(fill_u32(P.failed, 0, 1, st));
@@ -1147,14 +1223,7 @@ int enqueue_config(const hm_graph* H, NullPlan& P, uint32_t c0, hipStream_t st) 
   HM_HIP(hipGetLastError());
   if (P.E < 2) return HM_OK;
   for (int r = 0; r < P.sweeps; ++r) {
-    k_cfg_keys<<<grid_for(ne), 256, 0, st>>>(c0, P.R, P.E, uint32_t(r), P.seed, P.skeys, P.svals);
-    HM_HIP(hipGetLastError());
-    HM_TRY(radix_sort_ws(P.skeys, P.svals, P.skeys_tmp, P.svals_tmp, ne, 64, P.sort_ws, st));
-    if (P.R > 1) {
-      k_copy_of<<<grid_for(ne), 256, 0, st>>>(P.svals, ne, P.E, P.skeys);
-      HM_HIP(hipGetLastError());
-      HM_TRY(radix_sort_ws(P.skeys, P.svals, P.skeys_tmp, P.svals_tmp, ne, bits_for(P.R), P.sort_ws, st));
-    }
+    HM_TRY(enqueue_order(P, ne, P.E, uint64_t(r), kDomainConfig, c0, st));
     k_cfg_pairs<<<grid_for(uint64_t(P.R) * (P.E / 2)), 256, 0, st>>>(c0, P.R, P.E, P.T, uint32_t(r), P.seed, P.svals,
                                                                     H->all_off, P.members, P.cfg_tmp);
     HM_HIP(hipGetLastError());

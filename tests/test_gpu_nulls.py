@@ -44,9 +44,13 @@ def test_copies_match_oracle(hm, seed):
 
 
 def test_facetoface_copies_match_oracle(hm):
+    """Copies 0, 18 and 30 of seed 1 each hold stubs whose 64-bit keys share
+    their high 32 bits (2, 4 and 3 such groups among the 86,051 stubs), so
+    the device's ordering by (copy, high half) and then by the low half
+    within such runs is checked against the oracle's order by the full key."""
     h = W.cfg1_facetoface_k4(0)
     with hm.hm_graph_create(h.members, h.offsets, h.n_nodes) as g:
-        for copy in (0, 63):
+        for copy in (0, 18, 30, 63):
             m, o = hm.hm_null_export(g, 1, copy)
             wm, wo = nulls.stub_matching(h, 1, copy)
             assert np.array_equal(o, wo) and np.array_equal(m, wm), copy
