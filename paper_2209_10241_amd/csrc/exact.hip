@@ -68,26 +68,28 @@ __global__ void k_combine(unsigned long long* __restrict__ hist, int n_classes, 
                           int64_t* __restrict__ counts, IdShapes sh) {
   __shared__ unsigned long long ids[8];
   const int c = threadIdx.x;
-  unsigned long long m = 0, s = 0, g = 0;
+  // every copy is read before any is cleared, so that the loads go out
+  // together rather than each behind the previous store
+  unsigned long long m = 0, s = 0, g = 0, a = 0;
+#pragma unroll
   for (uint32_t q = 0; q < kHistCopies; ++q) {
-    unsigned long long* h = hist + uint64_t(q) * kExactHistStride;
+    const unsigned long long* h = hist + uint64_t(q) * kExactHistStride;
     m += h[kMain + c];
     s += h[kSub + c];
     g += h[kG2 + c];
+    if (sh.on && c < 7) a += h[kIdAcc + c];
+  }
+  __syncthreads();
+#pragma unroll
+  for (uint32_t q = 0; q < kHistCopies; ++q) {
+    unsigned long long* h = hist + uint64_t(q) * kExactHistStride;
     h[kMain + c] = 0;
     h[kSub + c] = 0;
     h[kG2 + c] = 0;
+    if (sh.on && c < 7) h[kIdAcc + c] = 0;
   }
   if (sh.on) {
-    if (c < 7) {
-      unsigned long long a = 0;
-      for (uint32_t q = 0; q < kHistCopies; ++q) {
-        unsigned long long* h = hist + uint64_t(q) * kExactHistStride + kIdAcc;
-        a += h[c];
-        h[c] = 0;
-      }
-      ids[c] = a;
-    }
+    if (c < 7) ids[c] = a;
     __syncthreads();
     g = id_shape_count(ids, sh, c);
   }

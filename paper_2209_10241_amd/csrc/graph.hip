@@ -70,7 +70,8 @@ __global__ void k_prepare(const uint32_t* __restrict__ members, const uint64_t* 
                           uint64_t n_edges, uint64_t n_members, uint32_t n_nodes, uint32_t* __restrict__ sm,
                           uint32_t* __restrict__ size, unsigned long long* __restrict__ hash,
                           uint8_t* __restrict__ ecode, FillRegions fills) {
-  multi_fill(fills);
+  // (the hyperedges first: their chain of dependent loads starts at once, and
+  // the fills' stores follow it)
   for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n_edges;
        i += uint64_t(gridDim.x) * blockDim.x) {
     const uint64_t b = offsets[i], e = offsets[i + 1];
@@ -116,6 +117,7 @@ __global__ void k_prepare(const uint32_t* __restrict__ members, const uint64_t* 
     }
     ecode[i] = uint8_t(err);
   }
+  multi_fill(fills);
 }
 
 __device__ inline bool same_tuple(const uint32_t* sm, const uint64_t* off, const uint32_t* size,
