@@ -479,6 +479,15 @@ __device__ void j2_walk_r(const View& v, const PairLinks& pl, const J2Ctx& c, ui
         pl_find(pl, ky, &lo, len);
         base[0] = uint32_t(lo);
         if (!*len) return;
+        // the run of {s, y}: {s, y, z} is a 3-node hyperedge exactly when z is
+        // among its third nodes (kept sorted), usually none
+        const unsigned long long ks =
+            y < c.s ? (((unsigned long long)y << 32) | c.s) : (((unsigned long long)c.s << 32) | y);
+        uint64_t slo;
+        uint32_t slen;
+        pl_find(pl, ks, &slo, &slen);
+        L.cnt[threadIdx.x][2] = uint32_t(slo);
+        L.cnt[threadIdx.x][3] = slen;
         // y ~ s holds exactly for the first part of the list (a node of T
         // adjacent to s was taken there); y is in T in the second part
         const uint32_t sy = j < c.ds, ty = j < c.ds ? uint32_t(j2_in_t(v, c, y)) : 1u;
@@ -494,18 +503,16 @@ __device__ void j2_walk_r(const View& v, const PairLinks& pl, const J2Ctx& c, ui
         // o ~ z and y ~ z come with the entry (its key is the pair {o, y})
         const uint32_t za = pl.adj[r];
         const uint32_t oz = c.o < y ? (za & 1u) : (za >> 1), yz = c.o < y ? (za >> 1) : (za & 1u);
-        Probe64 psz;
-        if (c.rs < 0) psz = probe2_start(v.hs2, c.s, z);
-        const Probe128 psyz = probe3_start(v.hs3, c.s, y, z);
-        Probe128 ptz;
-        if (c.any_t) ptz = probe3_start(v.hs3, c.s, c.o, z);
-        const uint32_t sz = c.rs >= 0 ? hub_adj(pl, c.rs, z) : uint32_t(probe64_end(v.hs2, psz));
-        const uint32_t tz = c.any_t && probe128_end(v.hs3, ptz);
+        // s ~ z; {s, o, z} a 3-node hyperedge exactly when z is in T, the run
+        // of {s, o} (sorted by third node)
+        const uint32_t sz = c.rs >= 0 ? hub_adj(pl, c.rs, z) : uint32_t(has2(v.hs2, c.s, z));
+        const uint32_t tz = c.any_t && run_find(pl, c.tlo, uint32_t(c.thi - c.tlo), z) != ~0ull;
         if (z < y && (sz | tz)) return;   // taken from z
         // as the histogram at o counts it (the smaller node first)
         const uint32_t olo = y < z ? oy : oz, ohi = y < z ? oz : oy;
         hadd(lut, h, 1u | (olo << 2) | (ohi << 5) | (yz << 7), 1);
-        if (probe128_end(v.hs3, psyz)) return;   // removed at s
+        const uint32_t slen = L.cnt[slot][3];
+        if (slen && run_find(pl, L.cnt[slot][2], slen, z) != ~0ull) return;   // removed at s
         // the pair {y, z} outside X whose set holds {o, y, z}, taken off
         if (ty | tz) return;
         hsub(lut, h, 1u | (sy << 1) | (oy << 2) | (sz << 4) | (oz << 5) | (yz << 7), 1);
