@@ -228,7 +228,23 @@ struct J2SparseLds {
   uint32_t seg_base[kThreads][3];
   uint32_t seg_len[kThreads][3];
   uint32_t cnt[kThreads][11];
+  // the sorted lists the correction walk searches, when they fit (at most
+  // kHeldList entries): T and the pairwise row of s
+  uint32_t t_list[1024], s_list[1024];
 };
+constexpr uint32_t kHeldList = 1024;
+
+// Whether z is in the ascending list l[0, n) (LDS).
+__device__ inline bool lds_find(const uint32_t* l, uint32_t n, uint32_t z) {
+  uint32_t lo = 0, hi = n;
+  while (hi > lo) {
+    const uint32_t m = (lo + hi) >> 1;
+    const uint32_t y = l[m];
+    if (y == z) return true;
+    if (y < z) lo = m + 1; else hi = m;
+  }
+  return false;
+}
 
 // Walk, for items [first, last) 256 at a time, the concatenated segments
 // seg(i) defines (up to three, each a start and a length), as one flat range
@@ -465,6 +481,12 @@ __device__ void j2_walk_t(const View& v, const PairLinks& pl, const J2Ctx& c, ui
 __device__ void j2_walk_r(const View& v, const PairLinks& pl, const J2Ctx& c, uint32_t first, uint32_t last,
                           J2SparseLds& L, const uint8_t* lut, unsigned long long* h) {
   const uint32_t sb = v.g2_off[c.s];
+  // T (the run of {s, o}) and the row of s, both ascending, into LDS when short
+  const uint32_t n_t = uint32_t(c.thi - c.tlo);
+  const bool hold_t = c.any_t && n_t <= kHeldList, hold_s = c.ds <= kHeldList;
+  for (uint32_t i = threadIdx.x; i < (hold_t ? n_t : 0u); i += kThreads) L.t_list[i] = pl.third[c.tlo + i];
+  for (uint32_t i = threadIdx.x; i < (hold_s ? c.ds : 0u); i += kThreads) L.s_list[i] = v.g2_adj[sb + i];
+  __syncthreads();
   auto y_of = [&](uint32_t j) { return j < c.ds ? v.g2_adj[sb + j] : j2_t_node(v, pl, c, c.tlo + (j - c.ds)); };
   block_flat(
       first, last, L,
@@ -505,8 +527,9 @@ __device__ void j2_walk_r(const View& v, const PairLinks& pl, const J2Ctx& c, ui
         const uint32_t oz = c.o < y ? (za & 1u) : (za >> 1), yz = c.o < y ? (za >> 1) : (za & 1u);
         // s ~ z; {s, o, z} a 3-node hyperedge exactly when z is in T, the run
         // of {s, o} (sorted by third node)
-        const uint32_t sz = c.rs >= 0 ? hub_adj(pl, c.rs, z) : uint32_t(has2(v.hs2, c.s, z));
-        const uint32_t tz = c.any_t && run_find(pl, c.tlo, uint32_t(c.thi - c.tlo), z) != ~0ull;
+        const uint32_t sz = hold_s ? uint32_t(lds_find(L.s_list, c.ds, z))
+                                   : (c.rs >= 0 ? hub_adj(pl, c.rs, z) : uint32_t(has2(v.hs2, c.s, z)));
+        const uint32_t tz = c.any_t && (hold_t ? lds_find(L.t_list, n_t, z) : run_find(pl, c.tlo, n_t, z) != ~0ull);
         if (z < y && (sz | tz)) return;   // taken from z
         // as the histogram at o counts it (the smaller node first)
         const uint32_t olo = y < z ? oy : oz, ohi = y < z ? oz : oy;
