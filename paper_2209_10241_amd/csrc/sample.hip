@@ -290,6 +290,9 @@ __device__ void block_flat(uint32_t first, uint32_t last, J2SparseLds& L, Seg se
   }
 }
 
+struct J2Ctx;
+__device__ inline void j2_hold_lists(const View& v, const PairLinks& pl, const J2Ctx& c, J2SparseLds& L);
+
 struct J2Ctx {
   uint32_t e0, s, o, ds, dO;
   int rs, ro;   // dense adjacency rows of s and o, or -1
@@ -388,9 +391,27 @@ __device__ inline bool j2_near_s(const View& v, const J2Ctx& c, uint32_t y) {
 // |N(t) n N(s)| and |N(t) n N(s) n N(o)| (the shorter of the two rows walked)
 // and |N(t) n N(o)| (likewise); those inside T from the shorter of N(t) and T
 // (all of them, and those after t, which take each joined pair inside T once).
+// T (the run of {s, o}) and the row of s, both ascending, into LDS when they
+// have at most kHeldList entries.  Every thread of the workgroup calls this.
+__device__ inline void j2_hold_lists(const View& v, const PairLinks& pl, const J2Ctx& c, J2SparseLds& L) {
+  const uint32_t n_t = uint32_t(c.thi - c.tlo), sb = v.g2_off[c.s];
+  const bool hold_t = c.any_t && n_t <= kHeldList, hold_s = c.ds <= kHeldList;
+  for (uint32_t i = threadIdx.x; i < (hold_t ? n_t : 0u); i += kThreads) L.t_list[i] = pl.third[c.tlo + i];
+  for (uint32_t i = threadIdx.x; i < (hold_s ? c.ds : 0u); i += kThreads) L.s_list[i] = v.g2_adj[sb + i];
+  __syncthreads();
+}
+
 __device__ void j2_walk_t(const View& v, const PairLinks& pl, const J2Ctx& c, uint32_t tc1, uint32_t tc2, uint32_t tc3,
                           uint32_t first, uint32_t last, J2SparseLds& L, const uint8_t* lut, unsigned long long* h) {
   const uint32_t n_t = uint32_t(c.thi - c.tlo);
+  j2_hold_lists(v, pl, c, L);
+  const bool hold_t = c.any_t && n_t <= kHeldList, hold_s = c.ds <= kHeldList;
+  auto s_adj = [&](uint32_t z) {
+    return hold_s ? uint32_t(lds_find(L.s_list, c.ds, z)) : j2_s_adj(v, pl, c, z);
+  };
+  auto in_t = [&](uint32_t y) {
+    return c.any_t && (hold_t ? lds_find(L.t_list, n_t, y) : has3(v.hs3, c.s, c.o, y));
+  };
   block_flat(
       first, last, L,
       [&](uint32_t j, uint32_t* base, uint32_t* len) {
@@ -408,7 +429,7 @@ __device__ void j2_walk_t(const View& v, const PairLinks& pl, const J2Ctx& c, ui
         const uint32_t dt = deg2_of(v, t);
         if (sg == 0) {
           const uint32_t z = v.g2_adj[pos];
-          const uint32_t hit = dt <= c.ds ? j2_s_adj(v, pl, c, z) : uint32_t(has2(v.hs2, t, z));
+          const uint32_t hit = dt <= c.ds ? s_adj(z) : uint32_t(has2(v.hs2, t, z));
           if (hit) {
             atomicAdd(&L.cnt[slot][0], 1u);
             if (j2_o_adj(v, pl, c, z)) atomicAdd(&L.cnt[slot][1], 1u);
@@ -420,8 +441,8 @@ __device__ void j2_walk_t(const View& v, const PairLinks& pl, const J2Ctx& c, ui
           uint32_t y, cy;
           if (dt <= n_t) {
             y = v.g2_adj[pos];
-            if (y == c.s || y == c.o || !j2_in_t(v, c, y)) return;
-            cy = j2_cls(v, pl, c, y);
+            if (y == c.s || y == c.o || !in_t(y)) return;
+            cy = s_adj(y) | (j2_o_adj(v, pl, c, y) << 1);
           } else {
             y = j2_t_node(v, pl, c, pos);
             if (y == t || !has2(v.hs2, t, y)) return;
@@ -481,12 +502,9 @@ __device__ void j2_walk_t(const View& v, const PairLinks& pl, const J2Ctx& c, ui
 __device__ void j2_walk_r(const View& v, const PairLinks& pl, const J2Ctx& c, uint32_t first, uint32_t last,
                           J2SparseLds& L, const uint8_t* lut, unsigned long long* h) {
   const uint32_t sb = v.g2_off[c.s];
-  // T (the run of {s, o}) and the row of s, both ascending, into LDS when short
   const uint32_t n_t = uint32_t(c.thi - c.tlo);
+  j2_hold_lists(v, pl, c, L);
   const bool hold_t = c.any_t && n_t <= kHeldList, hold_s = c.ds <= kHeldList;
-  for (uint32_t i = threadIdx.x; i < (hold_t ? n_t : 0u); i += kThreads) L.t_list[i] = pl.third[c.tlo + i];
-  for (uint32_t i = threadIdx.x; i < (hold_s ? c.ds : 0u); i += kThreads) L.s_list[i] = v.g2_adj[sb + i];
-  __syncthreads();
   auto y_of = [&](uint32_t j) { return j < c.ds ? v.g2_adj[sb + j] : j2_t_node(v, pl, c, c.tlo + (j - c.ds)); };
   block_flat(
       first, last, L,
@@ -512,7 +530,9 @@ __device__ void j2_walk_r(const View& v, const PairLinks& pl, const J2Ctx& c, ui
         L.cnt[threadIdx.x][3] = slen;
         // y ~ s holds exactly for the first part of the list (a node of T
         // adjacent to s was taken there); y is in T in the second part
-        const uint32_t sy = j < c.ds, ty = j < c.ds ? uint32_t(j2_in_t(v, c, y)) : 1u;
+        const uint32_t sy = j < c.ds,
+                       ty = j < c.ds ? uint32_t(c.any_t && (hold_t ? lds_find(L.t_list, n_t, y) : j2_in_t(v, c, y)))
+                                     : 1u;
         const uint32_t oy = j < c.ds ? j2_o_adj(v, pl, c, y) : (ycls >> 1);
         L.cnt[threadIdx.x][0] = y;
         L.cnt[threadIdx.x][1] = sy | (oy << 1) | (ty << 2);
