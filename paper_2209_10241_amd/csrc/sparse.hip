@@ -438,17 +438,9 @@ __global__ void k_b4_cost_keys(View v, PairLinks pl, uint64_t n3, unsigned long 
                                uint32_t* __restrict__ vals) {
   for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n3; i += uint64_t(gridDim.x) * blockDim.x) {
     const uint32_t a = v.e3[3 * i], b = v.e3[3 * i + 1], c = v.e3[3 * i + 2];
-    uint64_t lo;
-    uint32_t lab, lac, lbc;
-    pl_find(pl, ((unsigned long long)a << 32) | b, &lo, &lab);
-    pl_find(pl, ((unsigned long long)a << 32) | c, &lo, &lac);
-    pl_find(pl, ((unsigned long long)b << 32) | c, &lo, &lbc);
     const uint64_t dmin = min(deg2_of(v, a), min(deg2_of(v, b), deg2_of(v, c)));
     const uint32_t fa = v.i4_off[a + 1] - v.i4_off[a], fb = v.i4_off[b + 1] - v.i4_off[b],
                    fc = v.i4_off[c + 1] - v.i4_off[c];
-    (void)lab;
-    (void)lac;
-    (void)lbc;
     // (with the 4-node index, the 4-node hyperedges holding e are one lookup)
     const uint64_t cost = 2 * dmin + (pl.q_bits ? 0 : 6 * uint64_t(min(fa, min(fb, fc))));
     keys[i] = 0xFFFFFFFFull - min<uint64_t>(cost, 0xFFFFFFFFull);
