@@ -95,82 +95,6 @@ __global__ void __launch_bounds__(kThreads) k_sp_nodes(View v, const unsigned lo
   block_add(sp, acc + kAccPaw);
 }
 
-// 4-cycles: for the cycle's top node u in degree order and the node w
-// opposite it, the middle nodes are common neighbours of u and w that precede
-// u; cnt[w] counts them and the cycles through (u, w) are C(cnt[w], 2).  One
-// workgroup per u; the row of u is taken 256 neighbours at a time and the
-// rows of those that precede u are walked as one flat range.  cnt and the
-// list of touched w are private to the workgroup (N entries each, zero
-// between nodes).
-template <bool PER_EDGE>
-__global__ void __launch_bounds__(kThreads) k_sp_c4(View v, uint32_t* __restrict__ cnt_all,
-                                                    uint32_t* __restrict__ touched_all,
-                                                    unsigned long long* __restrict__ acc,
-                                                    const uint32_t* __restrict__ eid,
-                                                    unsigned long long* __restrict__ c4e) {
-  __shared__ uint32_t pre[kThreads + 1];
-  __shared__ uint32_t vv[kThreads];
-  __shared__ uint32_t wave_tot[kWavesPerBlock];
-  __shared__ uint32_t n_touched;
-  uint32_t* cnt = cnt_all + uint64_t(blockIdx.x) * v.N;
-  uint32_t* touched = touched_all + uint64_t(blockIdx.x) * v.N;
-  const uint32_t tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
-  unsigned long long total = 0;
-  for (uint32_t u = blockIdx.x; u < v.N; u += gridDim.x) {
-    const uint32_t ub = v.g2_off[u], ue = v.g2_off[u + 1];
-    if (ue - ub < 2) continue;
-    if (tid == 0) n_touched = 0;
-    // pass 0 counts the middle nodes per opposite node; with PER_EDGE, pass 1
-    // gives each wedge (u, x, w) the cnt[w] - 1 cycles it closes, on its two pairs
-    for (int pass = 0; pass < (PER_EDGE ? 2 : 1); ++pass) {
-      for (uint32_t c0 = ub; c0 < ue; c0 += kThreads) {
-        uint32_t x = 0, len = 0;
-        if (c0 + tid < ue) {
-          x = v.g2_adj[c0 + tid];
-          if (rank_less(v, x, u)) len = deg2_of(v, x);
-        }
-        uint32_t wtot;
-        uint32_t off = wave_exclusive_scan(len, &wtot);
-        if (lane == 0) wave_tot[wv] = wtot;
-        __syncthreads();
-        for (uint32_t q = 0; q < wv; ++q) off += wave_tot[q];
-        vv[tid] = x;
-        pre[tid] = off;
-        if (tid == kThreads - 1) pre[kThreads] = off + len;
-        __syncthreads();
-        const uint32_t work = pre[kThreads];
-        for (uint32_t t = tid; t < work; t += kThreads) {
-          uint32_t lo = 0, hi = kThreads;   // pre[lo] <= t < pre[hi]
-          while (hi - lo > 1) {
-            const uint32_t m = (lo + hi) >> 1;
-            if (pre[m] <= t) lo = m; else hi = m;
-          }
-          const uint32_t y = vv[lo];
-          const uint32_t pw = v.g2_off[y] + (t - pre[lo]);
-          const uint32_t w = v.g2_adj[pw];
-          if (w == u || !rank_less(v, w, u)) continue;
-          if (pass == 0) {
-            if (atomicAdd(&cnt[w], 1u) == 0u) touched[atomicAdd(&n_touched, 1u)] = w;
-          } else {
-            const uint32_t c = __hip_atomic_load(&cnt[w], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) - 1u;
-            if (c) {
-              atomicAdd(&c4e[eid[c0 + lo]], (unsigned long long)c);
-              atomicAdd(&c4e[eid[pw]], (unsigned long long)c);
-            }
-          }
-        }
-        __syncthreads();
-      }
-    }
-    const uint32_t nt = n_touched;
-    for (uint32_t i = tid; i < nt; i += kThreads) {
-      const unsigned long long c = atomicExch(&cnt[touched[i]], 0u);
-      total += c * (c - 1) / 2;
-    }
-    __syncthreads();
-  }
-  block_add(total, acc + kAccC4);
-}
 
 // 4-cycles without atomics per wedge: every wedge (u, x, w) with x and w
 // before the top node u in degree order becomes the key (u << B) | w; sorted,
@@ -208,7 +132,8 @@ __global__ void k_c4_tile_starts(const uint32_t* __restrict__ pos, const uint32_
 __global__ void __launch_bounds__(kThreads) k_c4_keys(View v, int B, const uint32_t* __restrict__ pos,
                                                       const uint32_t* __restrict__ start, uint64_t n2,
                                                       uint32_t n_pos, uint32_t n_tiles,
-                                                      unsigned long long* __restrict__ keys) {
+                                                      unsigned long long* __restrict__ keys,
+                                                      uint32_t* __restrict__ vals) {
   __shared__ uint32_t s_pos[kC4Tile + 2], s_top[kC4Tile + 2], s_row[kC4Tile + 2];
   const uint32_t tid = threadIdx.x, t = blockIdx.x;
   const uint32_t p0 = t * kC4Tile;
@@ -232,6 +157,64 @@ __global__ void __launch_bounds__(kThreads) k_c4_keys(View v, int B, const uint3
     }
     const uint32_t u = s_top[lo], w = v.g2_adj[s_row[lo] + (p - s_pos[lo])];
     keys[p] = (w == u || !rank_less(v, w, u)) ? kC4None : ((unsigned long long)u << B) | (unsigned long long)w;
+    vals[p] = p;
+  }
+}
+
+// Per-pair 4-cycle counts from the sorted wedge keys (vals: the walked
+// position of each key): a wedge (u, x, w) in a run of r >= 2 equal keys
+// closes r - 1 cycles, one with each other middle node of the run, and each
+// holds its pairs {u, x} (the pair whose walk the position belongs to) and
+// {x, w} (x's row entry).  One thread per key: it finds its run's ends by
+// galloping search (runs of hub pairs are long, most runs hold one key).
+__device__ inline uint64_t run_end(const unsigned long long* keys, uint64_t n, uint64_t i, unsigned long long key) {
+  uint64_t step = 1, lo = i;   // keys[lo] == key
+  while (lo + step < n && keys[lo + step] == key) {
+    lo += step;
+    step <<= 1;
+  }
+  uint64_t hi = min<uint64_t>(n, lo + step);   // keys[hi] != key or hi == n
+  while (hi - lo > 1) {
+    const uint64_t m = lo + ((hi - lo) >> 1);
+    if (keys[m] == key) lo = m; else hi = m;
+  }
+  return hi;
+}
+__device__ inline uint64_t run_begin(const unsigned long long* keys, uint64_t i, unsigned long long key) {
+  uint64_t step = 1, hi = i;   // keys[hi] == key
+  while (hi >= step && keys[hi - step] == key) {
+    hi -= step;
+    step <<= 1;
+  }
+  uint64_t lo = hi >= step ? hi - step : 0;   // keys[lo] != key, or lo == 0
+  if (keys[lo] == key) return lo;
+  while (hi - lo > 1) {
+    const uint64_t m = lo + ((hi - lo) >> 1);
+    if (keys[m] == key) hi = m; else lo = m;
+  }
+  return hi;
+}
+
+__global__ void k_c4_pair_counts(View v, const unsigned long long* __restrict__ keys, const uint32_t* __restrict__ vals,
+                                 uint64_t n, const uint32_t* __restrict__ pos, const uint32_t* __restrict__ start,
+                                 uint64_t n2, const uint32_t* __restrict__ eid, unsigned long long* __restrict__ c4e) {
+  for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += uint64_t(gridDim.x) * blockDim.x) {
+    const unsigned long long key = keys[i];
+    if (key == kC4None) continue;
+    const bool prev = i > 0 && keys[i - 1] == key, next = i + 1 < n && keys[i + 1] == key;
+    if (!prev && !next) continue;   // a run of one closes no cycle
+    const unsigned long long c = run_end(keys, n, i, key) - run_begin(keys, i, key) - 1;
+    const uint32_t p = vals[i];
+    // the pair whose walk holds position p: from the first pair of p's tile
+    uint64_t a = start[p / kC4Tile], b = min<uint64_t>(n2, a + kC4Tile + 2);   // pos[a] <= p < pos[b]
+    while (b - a > 1) {
+      const uint64_t m = (a + b) >> 1;
+      if (pos[m] <= p) a = m; else b = m;
+    }
+    const uint32_t x0 = v.e2[2 * a], x1 = v.e2[2 * a + 1];
+    const uint32_t x = rank_less(v, x0, x1) ? x0 : x1;
+    atomicAdd(&c4e[a], c);
+    atomicAdd(&c4e[eid[v.g2_off[x] + (p - pos[a])]], c);
   }
 }
 
@@ -259,6 +242,15 @@ int node_bits_of(uint32_t n) {
   while (b < 32 && (1ull << b) < n) ++b;
   return b;
 }
+
+// The sorted wedge keys of the 4-cycle count (see k_c4_keys).
+struct C4Keys {
+  unsigned long long* keys = nullptr;   // ascending, n_keys
+  uint32_t* vals = nullptr;             // the walked position of each key
+  uint32_t* pos = nullptr;              // first position of each pair of G2
+  uint32_t* start = nullptr;            // first pair of each tile of positions
+  uint64_t n_keys = 0;
+};
 
 // Neighbours that follow each node in degree order (outdeg zeroed by the caller).
 __global__ void k_sp_outdeg(View v, uint64_t n2, uint32_t* __restrict__ outdeg) {
@@ -317,26 +309,43 @@ __global__ void __launch_bounds__(kThreads) k_sp_k4(View v, uint64_t n2, uint32_
       nw += uint32_t(__popcll(m));
     }
     wave_sync();
-    uint32_t c = 0;
-    for (uint32_t i = 0; i + 1 < nw; ++i) {
-      const uint32_t wi = W[i];
-      for (uint32_t j = i + 1 + lane; j < nw; j += kWave) {
-        const uint32_t wj = W[j];
-        if (!has2(v.hs2, wi, wj)) continue;
-        ++c;
-        if (PER_EDGE) {
-          // the six pairs of {lo, hi, wi, wj}
-          atomicAdd(&k4e[e], 1ull);
-          atomicAdd(&k4e[eid[Wp[i]]], 1ull);
-          atomicAdd(&k4e[eid[Wp[j]]], 1ull);
-          atomicAdd(&k4e[eid[row_pos(v, hi, wi)]], 1ull);
-          atomicAdd(&k4e[eid[row_pos(v, hi, wj)]], 1ull);
-          const bool ci = deg2_of(v, wi) <= deg2_of(v, wj);
-          atomicAdd(&k4e[eid[ci ? row_pos(v, wi, wj) : row_pos(v, wj, wi)]], 1ull);
+    if (PER_EDGE) {
+      // Each lane owns slots s and counts, over every other slot t, the
+      // cliques {lo, hi, w_s, w_t}: the pairs {lo, w_s} and {hi, w_s} take
+      // that count once, the pair {w_s, w_t} one per clique (from s < t), and
+      // {lo, hi} the wavefront's total over the slots, halved.
+      unsigned long long twice = 0;
+      for (uint32_t s = lane; s < nw; s += kWave) {
+        const uint32_t ws = W[s];
+        uint32_t cs = 0;
+        for (uint32_t t = 0; t < nw; ++t) {
+          const uint32_t wt = W[t];
+          if (t == s || !has2(v.hs2, ws, wt)) continue;
+          ++cs;
+          if (s < t) {
+            const bool sw = deg2_of(v, ws) <= deg2_of(v, wt);
+            atomicAdd(&k4e[eid[sw ? row_pos(v, ws, wt) : row_pos(v, wt, ws)]], 1ull);
+          }
+        }
+        if (cs) {
+          atomicAdd(&k4e[eid[Wp[s]]], (unsigned long long)cs);
+          atomicAdd(&k4e[eid[row_pos(v, hi, ws)]], (unsigned long long)cs);
+          twice += cs;
         }
       }
+      twice = wave_sum(twice);
+      if (lane == 0 && twice) atomicAdd(&k4e[e], twice / 2);
+      total += twice / 2;
+    } else {
+      uint32_t c = 0;
+      for (uint32_t i = 0; i + 1 < nw; ++i) {
+        const uint32_t wi = W[i];
+        for (uint32_t j = i + 1 + lane; j < nw; j += kWave) {
+          if (has2(v.hs2, wi, W[j])) ++c;
+        }
+      }
+      total += wave_sum_u32(c);
     }
-    total += wave_sum_u32(c);
     wave_sync();
   }
   if (lane == 0) atomicAdd(acc + kAccK4, total);
@@ -609,6 +618,57 @@ unsigned grid_cap(uint64_t items, uint64_t per_block, unsigned cap) {
   return unsigned(std::max<uint64_t>(1, std::min<uint64_t>(g, cap)));
 }
 
+
+// The wedge keys of the 4-cycle count, built and sorted into scratch (one
+// host read-back: the number of walked positions).
+int c4_sorted_keys(const hm_graph* H, hipStream_t st, Scratch& tmp, C4Keys* out) {
+  const View v = view_of(H);
+  const uint64_t n2 = H->n_by_size[2];
+  *out = C4Keys{};
+  if (!n2) return HM_OK;
+  unsigned long long* walk = nullptr;
+  uint32_t* len = nullptr;
+  HM_TRY(tmp.get(&walk, 1));
+  HM_TRY(tmp.get(&len, n2));
+  HM_TRY(tmp.get(&out->pos, n2));
+  HM_TRY(fill_u64(walk, 0, 1, st));
+  k_c4_len<<<grid_cap(n2, 256, 2048), 256, 0, st>>>(v, n2, len, walk);
+  HM_HIP(hipGetLastError());
+  unsigned long long n_keys = 0;
+  HM_HIP(hipMemcpyAsync(&n_keys, walk, sizeof(n_keys), hipMemcpyDeviceToHost, st));
+  HM_HIP(hipStreamSynchronize(st));
+  const int B = node_bits_of(H->n_nodes);
+  if (n_keys >= 0xFFFFFFFFull || 2 * B > 63 || n2 >= 0xFFFFFFFFull) {
+    set_error("4-cycle wedges of %llu positions exceed the sort's range", n_keys);
+    return HM_EUNSUPPORTED;
+  }
+  if (!n_keys) return HM_OK;
+  const uint32_t n_tiles = uint32_t((n_keys + kC4Tile - 1) / kC4Tile);
+  unsigned long long* keys_tmp = nullptr;
+  uint32_t* vals_tmp = nullptr;
+  HM_TRY(tmp.get(&out->start, n_tiles));
+  HM_TRY(tmp.get(&out->keys, n_keys));
+  HM_TRY(tmp.get(&keys_tmp, n_keys));
+  HM_TRY(tmp.get(&out->vals, n_keys));
+  HM_TRY(tmp.get(&vals_tmp, n_keys));
+  HM_TRY(scan_exclusive_u32(len, out->pos, n2, nullptr, st));
+  k_c4_tile_starts<<<grid_cap(n2, 256, 4096), 256, 0, st>>>(out->pos, len, n2, out->start);
+  HM_HIP(hipGetLastError());
+  {
+    ProfileScope ps("k_c4_keys", st);
+    k_c4_keys<<<n_tiles, kThreads, 0, st>>>(v, B, out->pos, out->start, n2, uint32_t(n_keys), n_tiles, out->keys,
+                                           out->vals);
+  }
+  HM_HIP(hipGetLastError());
+  // the positions that are not wedges carry all ones and sort last
+  {
+    ProfileScope ps("c4_sort", st);
+    HM_TRY(radix_sort_pairs(out->keys, out->vals, keys_tmp, vals_tmp, n_keys, 2 * B + 1, st));
+  }
+  out->n_keys = n_keys;
+  return HM_OK;
+}
+
 // Workgroups of kThreads threads (no dynamic LDS) of `kernel` resident on the
 // current device at once.
 unsigned resident_blocks(const void* kernel) {
@@ -716,26 +776,26 @@ int ensure_edge_stats(hm_graph* H, hipStream_t st) {
   {
     Scratch tmp(st);
     unsigned long long *acc = nullptr, *tv = nullptr;
-    uint32_t *tri_e = nullptr, *cnt = nullptr, *touched = nullptr, *outdeg = nullptr, *dmax = nullptr,
-             *wlist = nullptr;
-    const unsigned g = grid_cap(N, 1, unsigned(std::max<uint64_t>(64, std::min<uint64_t>(512, (1ull << 27) / std::max<uint64_t>(N, 1)))));
+    uint32_t *tri_e = nullptr, *outdeg = nullptr, *dmax = nullptr, *wlist = nullptr;
     if (rc == HM_OK) rc = tmp.get(&acc, kAccN);
     if (rc == HM_OK) rc = tmp.get(&tv, N);
     if (rc == HM_OK) rc = tmp.get(&tri_e, n2);
-    if (rc == HM_OK) rc = tmp.get(&cnt, uint64_t(g) * N);
-    if (rc == HM_OK) rc = tmp.get(&touched, uint64_t(g) * N);
     if (rc == HM_OK) rc = tmp.get(&outdeg, N);
     if (rc == HM_OK) rc = tmp.get(&dmax, 1);
     if (rc == HM_OK) rc = fill_u64(acc, 0, kAccN, st);
     if (rc == HM_OK) rc = fill_u64(tv, 0, N, st);
-    if (rc == HM_OK) rc = fill_u32(cnt, 0, uint64_t(g) * N, st);
     if (rc == HM_OK) rc = fill_u32(dmax, 0, 1, st);
     if (rc == HM_OK && n2) {
       k_sp_edge_tri<<<grid_cap(n2, kWavesPerBlock, 2048), kThreads, 0, st>>>(v, n2, tri_e, tv, acc);
       k_es_widen<<<grid_cap(n2, 256, 2048), 256, 0, st>>>(tri_e, n2, es);
       k_es_sums<<<grid_cap(n2, kWavesPerBlock, 2048), kThreads, 0, st>>>(v, n2, H->g2_eid, tri_e, es + 3 * n2,
                                                                          es + 4 * n2, es + 5 * n2);
-      k_sp_c4<true><<<g, kThreads, 0, st>>>(v, cnt, touched, acc, H->g2_eid, es + 2 * n2);
+      // per-pair 4-cycles from the sorted wedge keys
+      C4Keys ck;
+      if (rc == HM_OK) rc = c4_sorted_keys(H, st, tmp, &ck);
+      if (rc == HM_OK && ck.n_keys)
+        k_c4_pair_counts<<<grid_cap(ck.n_keys, 256, 4096), 256, 0, st>>>(v, ck.keys, ck.vals, ck.n_keys, ck.pos,
+                                                                        ck.start, n2, H->g2_eid, es + 2 * n2);
       if (fill_u32(outdeg, 0, N, st) != HM_OK) rc = HM_EDEVICE;
       k_sp_outdeg<<<grid_cap(n2, 256, 2048), 256, 0, st>>>(v, n2, outdeg);
       if (hipGetLastError() != hipSuccess) rc = HM_EDEVICE;
@@ -1073,50 +1133,13 @@ int count_sparse(const hm_graph* H, int k, hipStream_t st) {
   cls.clique = t.lut4[kPairBits4];
   if (k == 4 && n2) {
     // 4-cycles: wedge keys, sorted, counted by runs
-    unsigned long long* walk = nullptr;
-    uint32_t *len = nullptr, *pos = nullptr;
-    HM_TRY(tmp.get(&walk, 1));
-    HM_TRY(tmp.get(&len, n2));
-    HM_TRY(tmp.get(&pos, n2));
-    HM_TRY(fill_u64(walk, 0, 1, st));
-    k_c4_len<<<grid_cap(n2, 256, 2048), 256, 0, st>>>(v, n2, len, walk);
+    C4Keys ck;
+    HM_TRY(c4_sorted_keys(H, st, tmp, &ck));
+    if (ck.n_keys) {
+      ProfileScope ps("k_c4_runs", st);
+      k_c4_runs<<<grid_cap(ck.n_keys, 256, 4096), 256, 0, st>>>(ck.keys, ck.n_keys, kC4None, acc + kAccC4);
+    }
     HM_HIP(hipGetLastError());
-    unsigned long long n_keys = 0;
-    HM_HIP(hipMemcpyAsync(&n_keys, walk, sizeof(n_keys), hipMemcpyDeviceToHost, st));
-    HM_HIP(hipStreamSynchronize(st));
-    const int B = node_bits_of(H->n_nodes);
-    if (n_keys >= 0xFFFFFFFFull || 2 * B > 63 || n2 >= 0xFFFFFFFFull) {
-      set_error("4-cycle wedges of %llu positions exceed the sort's range", n_keys);
-      return HM_EUNSUPPORTED;
-    }
-    if (n_keys) {
-      const uint32_t n_tiles = uint32_t((n_keys + kC4Tile - 1) / kC4Tile);
-      unsigned long long *keys = nullptr, *keys_tmp = nullptr;
-      uint32_t *vals = nullptr, *vals_tmp = nullptr, *start = nullptr;
-      HM_TRY(tmp.get(&start, n_tiles));
-      HM_TRY(tmp.get(&keys, n_keys));
-      HM_TRY(tmp.get(&keys_tmp, n_keys));
-      HM_TRY(tmp.get(&vals, n_keys));
-      HM_TRY(tmp.get(&vals_tmp, n_keys));
-      HM_TRY(scan_exclusive_u32(len, pos, n2, nullptr, st));
-      k_c4_tile_starts<<<grid_cap(n2, 256, 4096), 256, 0, st>>>(pos, len, n2, start);
-      HM_HIP(hipGetLastError());
-      {
-        ProfileScope ps("k_c4_keys", st);
-        k_c4_keys<<<n_tiles, kThreads, 0, st>>>(v, B, pos, start, n2, uint32_t(n_keys), n_tiles, keys);
-      }
-      HM_HIP(hipGetLastError());
-      // the positions that are not wedges carry all ones and sort last
-      {
-        ProfileScope ps("c4_sort", st);
-        HM_TRY(radix_sort_pairs(keys, vals, keys_tmp, vals_tmp, n_keys, 2 * B + 1, st));
-      }
-      {
-        ProfileScope ps("k_c4_runs", st);
-        k_c4_runs<<<grid_cap(n_keys, 256, 4096), 256, 0, st>>>(keys, n_keys, kC4None, acc + kAccC4);
-      }
-      HM_HIP(hipGetLastError());
-    }
     // 4-cliques
     uint32_t *outdeg = nullptr, *dmax = nullptr;
     HM_TRY(tmp.get(&outdeg, H->n_nodes));
