@@ -66,18 +66,22 @@ constexpr int kHistWords = 768;
 constexpr int kIdAcc = 768;  // the seven sums of the identity route for (c) (exact counts only)
 
 // (a) at order 4: the pattern of a 4-node hyperedge; local positions a..d = 0..3
+// (the four 3-node probes are started together and resolved afterwards, so
+// that their first loads are in flight at once)
 __device__ inline uint32_t a4_pattern(const View& v, uint32_t a, uint32_t b, uint32_t c, uint32_t d) {
+  const Probe128 q3 = probe128_start(v.hs3, key3(a, b, c)), q6 = probe128_start(v.hs3, key3(a, b, d)),
+                 q8 = probe128_start(v.hs3, key3(a, c, d)), q9 = probe128_start(v.hs3, key3(b, c, d));
   uint32_t p = 1u << 10;
   p |= pair_bit(v.hs2, v.bits, v.W, a, b) << 0;
   p |= pair_bit(v.hs2, v.bits, v.W, a, c) << 1;
   p |= pair_bit(v.hs2, v.bits, v.W, b, c) << 2;
-  p |= uint32_t(set128_has(v.hs3, key3(a, b, c))) << 3;
   p |= pair_bit(v.hs2, v.bits, v.W, a, d) << 4;
   p |= pair_bit(v.hs2, v.bits, v.W, b, d) << 5;
-  p |= uint32_t(set128_has(v.hs3, key3(a, b, d))) << 6;
   p |= pair_bit(v.hs2, v.bits, v.W, c, d) << 7;
-  p |= uint32_t(set128_has(v.hs3, key3(a, c, d))) << 8;
-  p |= uint32_t(set128_has(v.hs3, key3(b, c, d))) << 9;
+  p |= uint32_t(probe128_end(v.hs3, q3)) << 3;
+  p |= uint32_t(probe128_end(v.hs3, q6)) << 6;
+  p |= uint32_t(probe128_end(v.hs3, q8)) << 8;
+  p |= uint32_t(probe128_end(v.hs3, q9)) << 9;
   return p;
 }
 
