@@ -169,6 +169,39 @@ def scale_estimate(raw: np.ndarray, k: int, n_by_size: dict, s_by_size: dict) ->
     return est
 
 
+def estimator_moments(h, k: int, s_by_size: dict):
+    """Variance and excess kurtosis, per class, of Algorithm 4's corrected
+    estimate with S_j draws with replacement from each stratum (Section 5).
+
+    A class m is estimated from the stratum j of its largest hyperedges:
+    est_m = |E_j| / (S_j countmax_m) * sum over the S_j draws of n_m(e), with
+    n_m(e) the raw count of one sample e and the draws independent and
+    uniform on E_j.  So Var(est_m) = |E_j|^2 / (S_j countmax_m^2) * v_m, v_m the
+    variance of n_m(e) over E_j, and the excess kurtosis of the sum is that
+    of n_m(e) divided by S_j.  n_m(e) comes from sampled_raw with e as the
+    only sample.  Returns (var, kurt), float64; 0 where v_m = 0 or S_j = 0.
+    """
+    nh = h if isinstance(h, Normalised) else normalise(h)
+    t = table(k)
+    var = np.zeros(t.n_classes)
+    kurt = np.zeros(t.n_classes)
+    for j in range(2, k + 1):
+        n_j, S = nh.count(j), s_by_size.get(j, 0)
+        if n_j == 0 or S == 0:
+            continue
+        per = np.array([sampled_raw(nh, k, {j: [e]}) for e in range(n_j)], dtype=np.float64)
+        for m in range(t.n_classes):
+            if t.maxcard[m] != j:
+                continue
+            x = per[:, m]
+            v = x.var()
+            if v == 0.0:
+                continue
+            var[m] = float(n_j) ** 2 * v / (float(S) * t.countmax[m] ** 2)
+            kurt[m] = (((x - x.mean()) ** 4).mean() / v ** 2 - 3.0) / S
+    return var, kurt
+
+
 def class_canon_c(k: int) -> list:
     buf = np.zeros(256, dtype=np.uint32)
     n = lib().oracle_class_canon(k, buf)

@@ -174,6 +174,37 @@ def test_unbiased_over_32_seeds(hm):
     assert mre < 0.05
 
 
+def test_variance_matches_closed_form(hm):
+    """The spread of the sampler's estimate over 3000 seeds is that of S_j
+    independent uniform draws with replacement from each stratum (Section 5):
+    the per-class sample variance agrees with the oracle's |E_j|^2 v_m /
+    (S_j countmax_m^2) within 5 standard errors of a variance estimate, and
+    is 0 where that is.  Half of each stratum is drawn, so draws without
+    replacement would show as a variance about half as large."""
+    import torch
+    h = W.random_small(700, 16, 70, {2: 0.5, 3: 0.3, 4: 0.2})
+    nh = core.normalise(h)
+    k, R = 4, 3000
+    n_j = {j: nh.count(j) for j in range(2, k + 1)}
+    S = core.sample_sizes(n_j, k, 0.5)
+    var, kurt = core.estimator_moments(nh, k, S)
+    n = hm.hm_num_classes(k)
+    est = torch.empty((R, n), dtype=torch.float32, device="cuda")
+    raw = torch.empty((R, n), dtype=torch.int64, device="cuda")
+    with _graph(hm, h) as g:
+        for seed in range(R):
+            hm.count_sampled(g, k, 0.5, 7000 + seed, 0, est=est[seed], raw=raw[seed])
+        runs = est.cpu().numpy().astype(np.float64)
+    s2 = runs.var(axis=0, ddof=1)
+    assert np.all(s2[var == 0] == 0)
+    on = var > 0
+    assert on.sum() >= 10
+    rel = s2[on] / var[on] - 1.0
+    tol = 5.0 * np.sqrt(2.0 / (R - 1) + np.maximum(kurt[on], 0.0) / R)
+    print(f"variance over {R} seeds: max |rel| / tol {np.abs(rel / tol).max():.2f}")
+    assert np.all(np.abs(rel) < tol), (rel[np.abs(rel) >= tol], tol[np.abs(rel) >= tol])
+
+
 @pytest.fixture
 def queued(hm):
     """No bit rows and the smallest work chunks: the long walks of every sample

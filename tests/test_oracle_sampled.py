@@ -115,6 +115,36 @@ def test_estimator_is_unbiased():
     assert stats.mean_relative_error(runs, exact) < 0.5
 
 
+def test_estimator_variance_matches_closed_form():
+    """The spread of the corrected estimate over seeds is that of S_j
+    independent uniform draws with replacement (Section 5): for every class
+    the sample variance over 3000 seeds agrees with |E_j|^2 v_m / (S_j
+    countmax_m^2) within 5 standard errors of a variance estimate
+    (sqrt(2 / (R - 1) + kurtosis / R) relative), and is 0 where v_m is.  With
+    half of each stratum drawn, draws without replacement would shrink the
+    variance by about half (by (|E_j| - S_j) / (|E_j| - 1)), several times
+    the tolerance; a biased index or a wrong S_j in the correction would
+    change it too."""
+    h = W.random_small(700, 16, 70, {2: 0.5, 3: 0.3, 4: 0.2})
+    nh = core.normalise(h)
+    k = 4
+    n_j = _strata(nh, k)
+    S = {j: max(1, n_j[j] // 2) for j in n_j}
+    var, kurt = core.estimator_moments(nh, k, S)
+    R = 3000
+    runs = []
+    for seed in range(R):
+        samples = {j: philox.stratum_draws(seed, j, n_j[j], S[j]) for j in n_j}
+        runs.append(core.scale_estimate(core.sampled_raw(nh, k, samples), k, n_j, S))
+    s2 = np.array(runs).var(axis=0, ddof=1)
+    assert np.all(s2[var == 0] == 0)
+    on = var > 0
+    assert on.sum() >= 10
+    rel = s2[on] / var[on] - 1.0
+    tol = 5.0 * np.sqrt(2.0 / (R - 1) + np.maximum(kurt[on], 0.0) / R)
+    assert np.all(np.abs(rel) < tol), (rel[np.abs(rel) >= tol], tol[np.abs(rel) >= tol])
+
+
 def test_unsampled_stratum_reports_zero():
     h = W.from_lists([[0, 1, 2, 3], [0, 1], [1, 2], [2, 3]], 4)
     raw = core.sampled_raw(h, 4, {2: [0]})
