@@ -183,17 +183,17 @@ struct BlockInfo {
   int device;
   size_t bytes;
 };
+// the blocks of one dfree_on call, free once its event has completed
 struct Pending {
-  void* p;
-  BlockInfo info;
   hipEvent_t ev;
+  int device;
+  std::vector<std::pair<void*, BlockInfo>> blocks;
 };
 std::mutex g_pool_mu;
 std::map<std::pair<int, size_t>, std::vector<void*>> g_free;
 std::unordered_map<void*, BlockInfo> g_live;
 std::vector<Pending> g_pending;
 std::map<int, std::vector<hipEvent_t>> g_events;   // idle events per device
-std::unordered_map<hipEvent_t, size_t> g_event_users;   // pending blocks per event
 size_t g_cached_bytes = 0;
 constexpr size_t kMaxCachedBytes = size_t(8) << 30;
 
@@ -213,23 +213,32 @@ void cache_block(void* p, const BlockInfo& info) {
   g_cached_bytes += info.bytes;
 }
 
-// caller holds g_pool_mu: pending blocks whose event has completed become free
+// caller holds g_pool_mu: pending blocks whose event has completed become
+// free (one query per release batch)
 void reap_pending() {
   for (size_t i = 0; i < g_pending.size();) {
     Pending& q = g_pending[i];
     if (hipEventQuery(q.ev) == hipSuccess) {
-      cache_block(q.p, q.info);
-      if (--g_event_users[q.ev] == 0) {
-        g_event_users.erase(q.ev);
-        g_events[q.info.device].push_back(q.ev);
-      }
-      q = g_pending.back();
+      for (auto& b : q.blocks) cache_block(b.first, b.second);
+      g_events[q.device].push_back(q.ev);
+      q = std::move(g_pending.back());
       g_pending.pop_back();
     } else {
       ++i;
     }
   }
   (void)hipGetLastError();
+}
+
+// caller holds g_pool_mu: a cached block of (dev, cls), or null
+void* take_cached(int dev, size_t cls) {
+  auto it = g_free.find({dev, cls});
+  if (it == g_free.end() || it->second.empty()) return nullptr;
+  void* p = it->second.back();
+  it->second.pop_back();
+  g_cached_bytes -= cls;
+  g_live[p] = BlockInfo{dev, cls};
+  return p;
 }
 }  // namespace
 
@@ -242,16 +251,14 @@ int dalloc(void** p, size_t bytes) {
   }
   const size_t cls = size_class(bytes ? bytes : 1);
   {
+    // a cached block, else one whose release has completed since
     std::lock_guard<std::mutex> lock(g_pool_mu);
-    if (!g_pending.empty()) reap_pending();
-    auto it = g_free.find({dev, cls});
-    if (it != g_free.end() && !it->second.empty()) {
-      *p = it->second.back();
-      it->second.pop_back();
-      g_cached_bytes -= cls;
-      g_live[*p] = BlockInfo{dev, cls};
-      return HM_OK;
+    *p = take_cached(dev, cls);
+    if (!*p && !g_pending.empty()) {
+      reap_pending();
+      *p = take_cached(dev, cls);
     }
+    if (*p) return HM_OK;
   }
   hipError_t e = hipMalloc(p, cls);
   if (e != hipSuccess) {
@@ -305,8 +312,7 @@ void dfree_on(void* const* ps, size_t n, hipStream_t st) {
     for (auto& b : blocks) cache_block(b.first, b.second);
     return;
   }
-  g_event_users[ev] += blocks.size();
-  for (auto& b : blocks) g_pending.push_back(Pending{b.first, b.second, ev});
+  g_pending.push_back(Pending{ev, dev, std::move(blocks)});
 }
 
 void dfree_on(void* p, hipStream_t st) { dfree_on(&p, 1, st); }

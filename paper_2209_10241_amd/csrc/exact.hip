@@ -139,7 +139,7 @@ __global__ void __launch_bounds__(kExact4Threads) k_exact4_bits(ExactArgs a) {
   View v = a.v;
   uint32_t* b4_sets = dyn_lds;
   if (LB) {
-    // the rows start 16 * W words in: 16-byte aligned
+    // the rows start 16 * (4 * W + 64) words in: 16-byte aligned
     uint32_t* rows = dyn_lds + kExact4Waves * b4_set_words(v.W);
     const uint32_t n = v.N * v.W, n4 = n / 4;
     const uint4* src = reinterpret_cast<const uint4*>(v.bits);

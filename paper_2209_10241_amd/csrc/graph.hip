@@ -566,17 +566,30 @@ __device__ void rows_from_bits(const uint32_t* __restrict__ bits, uint32_t n, ui
 // Incidence lists of the 3- and 4-node hyperedges (positions in any order):
 // hyperedge i fills through the cursor of copy i & (R - 1) of each member,
 // the copy its degree was counted in (workgroup `block` of `n_blocks`).
+// With bit rows (oth3, oth4 not null) each entry also gets the hyperedge's
+// other members.
 __device__ void inc_fill(const uint32_t* __restrict__ e3, uint64_t n3, uint32_t* cur3, uint32_t* idx3,
                          const uint32_t* __restrict__ e4, uint64_t n4, uint32_t* cur4, uint32_t* idx4, uint32_t R,
-                         uint32_t block, uint32_t n_blocks) {
+                         uint32_t* __restrict__ oth3, unsigned long long* __restrict__ oth4, uint32_t block,
+                         uint32_t n_blocks) {
   for (uint64_t i = uint64_t(block) * blockDim.x + threadIdx.x; i < n3 + n4; i += uint64_t(n_blocks) * blockDim.x) {
     if (i < n3) {
       const uint32_t cp = uint32_t(i) & (R - 1);
-      for (int j = 0; j < 3; ++j) idx3[atomicAdd(&cur3[uint64_t(e3[3 * i + j]) * R + cp], 1u)] = uint32_t(i);
+      const uint32_t m[3] = {e3[3 * i], e3[3 * i + 1], e3[3 * i + 2]};
+      for (int j = 0; j < 3; ++j) {
+        const uint32_t at = atomicAdd(&cur3[uint64_t(m[j]) * R + cp], 1u);
+        idx3[at] = uint32_t(i);
+        if (oth3) oth3[at] = others3(m, j);
+      }
     } else {
       const uint64_t q = i - n3;
       const uint32_t cp = uint32_t(q) & (R - 1);
-      for (int j = 0; j < 4; ++j) idx4[atomicAdd(&cur4[uint64_t(e4[4 * q + j]) * R + cp], 1u)] = uint32_t(q);
+      const uint32_t m[4] = {e4[4 * q], e4[4 * q + 1], e4[4 * q + 2], e4[4 * q + 3]};
+      for (int j = 0; j < 4; ++j) {
+        const uint32_t at = atomicAdd(&cur4[uint64_t(m[j]) * R + cp], 1u);
+        idx4[at] = uint32_t(q);
+        if (oth4) oth4[at] = others4(m, j);
+      }
     }
   }
 }
@@ -587,7 +600,7 @@ __global__ void k_inc_fill(const uint32_t* __restrict__ e3, uint32_t* cur3, uint
                            const uint32_t* __restrict__ e4, uint32_t* cur4, uint32_t* idx4, uint32_t R,
                            const unsigned long long* __restrict__ totals) {
   if (totals[kTileN]) return;
-  inc_fill(e3, totals[2], cur3, idx3, e4, totals[3], cur4, idx4, R, blockIdx.x, gridDim.x);
+  inc_fill(e3, totals[2], cur3, idx3, e4, totals[3], cur4, idx4, R, nullptr, nullptr, blockIdx.x, gridDim.x);
 }
 
 // Pairwise rows from the bit rows (workgroups [0, row_blocks)) and the
@@ -596,12 +609,13 @@ __global__ void k_rows_and_incidence(const uint32_t* __restrict__ bits, uint32_t
                                      const uint32_t* __restrict__ row_off, uint32_t* __restrict__ adj,
                                      uint32_t row_blocks, const uint32_t* __restrict__ e3, uint32_t* cur3,
                                      uint32_t* idx3, const uint32_t* __restrict__ e4, uint32_t* cur4, uint32_t* idx4,
-                                     uint32_t R, const unsigned long long* __restrict__ totals) {
+                                     uint32_t R, uint32_t* oth3, unsigned long long* oth4,
+                                     const unsigned long long* __restrict__ totals) {
   if (totals[kTileN]) return;
   if (blockIdx.x < row_blocks)
     rows_from_bits(bits, n, W, row_off, adj, blockIdx.x, row_blocks);
   else
-    inc_fill(e3, totals[2], cur3, idx3, e4, totals[3], cur4, idx4, R, blockIdx.x - row_blocks,
+    inc_fill(e3, totals[2], cur3, idx3, e4, totals[3], cur4, idx4, R, oth3, oth4, blockIdx.x - row_blocks,
              gridDim.x - row_blocks);
 }
 
@@ -629,11 +643,48 @@ unsigned grid_for(uint64_t n, unsigned block = 256) {
   return unsigned(g);
 }
 
+// Arrays carved from one device block, each 256-byte aligned: one call to the
+// caching allocator instead of one per array (the build's host time before
+// its first launch is mostly such calls).  Above kCarveMaxBytes in all, where
+// a power-of-two block would waste much memory and the calls cost little
+// beside the work, each array gets a block of its own.
+constexpr size_t kCarveMaxBytes = size_t(64) << 20;
+struct Carve {
+  std::vector<std::pair<void**, size_t>> parts;
+  template <typename T>
+  void add(T** p, uint64_t count) {
+    parts.emplace_back(reinterpret_cast<void**>(p), (size_t(count ? count : 1) * sizeof(T) + 255) & ~size_t(255));
+  }
+  // sets every added array; the blocks taken go to *blocks (one when carved)
+  int take(std::vector<void*>* blocks) {
+    size_t total = 0;
+    for (auto& q : parts) total += q.second;
+    if (total <= kCarveMaxBytes) {
+      void* base = nullptr;
+      HM_TRY(dalloc(&base, total));
+      blocks->push_back(base);
+      char* at = static_cast<char*>(base);
+      for (auto& q : parts) {
+        *q.first = at;
+        at += q.second;
+      }
+    } else {
+      for (auto& q : parts) {
+        HM_TRY(dalloc(q.first, q.second));
+        blocks->push_back(*q.first);
+      }
+    }
+    parts.clear();
+    return HM_OK;
+  }
+};
+
 // RAII holder for temporary device buffers of the build, released after the
 // work enqueued on the build's stream
 struct Temps {
   hipStream_t st;
   std::vector<void*> ptrs;
+  Carve staged;
   explicit Temps(hipStream_t s) : st(s) {}
   ~Temps() { dfree_on(ptrs.data(), ptrs.size(), st); }
   template <typename T>
@@ -644,6 +695,12 @@ struct Temps {
     *p = static_cast<T*>(q);
     return HM_OK;
   }
+  // stage(): set by the next commit(), which carves every staged array from one block
+  template <typename T>
+  void stage(T** p, uint64_t count) {
+    staged.add(p, count);
+  }
+  int commit() { return staged.take(&ptrs); }
 };
 
 template <typename T>
@@ -786,15 +843,17 @@ int build(hm_graph* H, const uint32_t* members_in, const uint64_t* offsets_in, u
   // dedup table: a lower load (1/8 instead of 1/2) shortens the longest probe
   // chain, which sets the dedup kernel's time; kept at 1/2 for large inputs
   const unsigned long long cap = pow2_capacity(E <= (1ull << 20) ? 4 * E : E);
-  HM_TRY(tmp.get(&dev_totals, kTileN + 1));
-  HM_TRY(tmp.get(&sm, n_members));
-  HM_TRY(tmp.get(&size, E));
-  HM_TRY(tmp.get(&hash, E));
-  HM_TRY(tmp.get(&slots, cap));
-  HM_TRY(tmp.get(&slot_of, E));
-  HM_TRY(tmp.get(&first, E));
-  HM_TRY(tmp.get(&ecode, E));
-  HM_TRY(tmp.get(&tile_cnt, n_tiles * kTileS));
+  tmp.stage(&dev_totals, kTileN + 1);
+  tmp.stage(&sm, n_members);
+  tmp.stage(&size, E);
+  tmp.stage(&hash, E);
+  tmp.stage(&slots, cap);
+  tmp.stage(&slot_of, E);
+  tmp.stage(&first, E);
+  tmp.stage(&ecode, E);
+  tmp.stage(&tile_cnt, n_tiles * kTileS);
+  // (in one pass they share a block with the temporaries allocate() stages)
+  if (!one_pass) HM_TRY(tmp.commit());
   PinnedReport rep;
   HM_TRY(rep.take());
   Report* rep_dev = nullptr;
@@ -810,35 +869,44 @@ int build(hm_graph* H, const uint32_t* members_in, const uint64_t* offsets_in, u
   uint32_t *deg2 = nullptr, *deg3 = nullptr, *deg4 = nullptr, *cur3 = nullptr, *cur4 = nullptr;
   auto allocate = [&](uint64_t n2, uint64_t n3, uint64_t n4, uint64_t n_unique, uint64_t n_unique_members,
                       FillList& fl) -> int {
-    HM_TRY(owned(&H->e2, 2 * n2));
-    HM_TRY(owned(&H->e3, 3 * n3));
-    HM_TRY(owned(&H->e4, 4 * n4));
-    HM_TRY(owned(&H->all_members, n_unique_members));
-    HM_TRY(owned(&H->all_off, n_unique + 1));
+    Carve own;
+    own.add(&H->e2, 2 * n2);
+    own.add(&H->e3, 3 * n3);
+    own.add(&H->e4, 4 * n4);
+    own.add(&H->all_members, n_unique_members);
+    own.add(&H->all_off, n_unique + 1);
     const unsigned long long c2 = pow2_capacity(n2), c3 = pow2_capacity(n3), c4 = pow2_capacity(n4);
-    HM_TRY(owned(&H->hs2.slot, c2));
-    HM_TRY(owned(&H->hs3.slot, 2 * c3));
-    HM_TRY(owned(&H->hs4.slot, 2 * c4));
+    own.add(&H->hs2.slot, c2);
+    own.add(&H->hs3.slot, 2 * c3);
+    own.add(&H->hs4.slot, 2 * c4);
     H->hs2.mask = c2 - 1;
     H->hs3.mask = c3 - 1;
     H->hs4.mask = c4 - 1;
     if (keep_bits) {
       H->words = (H->n_nodes + 31) / 32;
-      HM_TRY(owned(&H->bits, N * H->words));
+      own.add(&H->bits, N * H->words);
+      own.add(&H->i3_oth, 3 * n3);
+      own.add(&H->i4_oth, 4 * n4);
     }
-    HM_TRY(tmp.get(&deg2, NR));
-    HM_TRY(tmp.get(&deg3, NR));
-    HM_TRY(tmp.get(&deg4, NR));
-    HM_TRY(tmp.get(&cur3, NR + 1));
-    HM_TRY(tmp.get(&cur4, NR + 1));
-    HM_TRY(owned(&H->g2_off, N + 1));
-    HM_TRY(owned(&H->g2_adj, 2 * n2));
-    HM_TRY(owned(&H->i3_off, N + 1));
-    HM_TRY(owned(&H->i3_idx, 3 * n3));
-    HM_TRY(owned(&H->i4_off, N + 1));
-    HM_TRY(owned(&H->i4_idx, 4 * n4));
-    HM_TRY(owned(&H->hist, uint64_t(kHistCopies) * kExactHistStride));
-    HM_TRY(owned(&H->sample_hist, uint64_t(kHistCopies) * kSampleHistStride + 8));
+    tmp.stage(&deg2, NR);
+    tmp.stage(&deg3, NR);
+    tmp.stage(&deg4, NR);
+    tmp.stage(&cur3, NR + 1);
+    tmp.stage(&cur4, NR + 1);
+    own.add(&H->g2_off, N + 1);
+    own.add(&H->g2_adj, 2 * n2);
+    own.add(&H->i3_off, N + 1);
+    own.add(&H->i3_idx, 3 * n3);
+    own.add(&H->i4_off, N + 1);
+    own.add(&H->i4_idx, 4 * n4);
+    own.add(&H->hist, uint64_t(kHistCopies) * kExactHistStride);
+    own.add(&H->sample_hist, uint64_t(kHistCopies) * kSampleHistStride + 8);
+    std::vector<void*> blocks;
+    const int rc = own.take(&blocks);
+    // carved: the graph frees the one block; else every array is its own
+    H->arena = blocks.size() == 1 ? blocks[0] : nullptr;
+    HM_TRY(rc);
+    HM_TRY(tmp.commit());
     fl.add(H->hs2.slot, c2, kEmpty64, 1);
     fl.add(H->hs3.slot, 2 * c3, kEmpty64, 1);
     fl.add(H->hs4.slot, 2 * c4, kEmpty64, 1);
@@ -852,9 +920,10 @@ int build(hm_graph* H, const uint32_t* members_in, const uint64_t* offsets_in, u
     return HM_OK;
   };
   // the dedup table (and in one pass every output table), filled by k_prepare
+  // (in one pass the table is carved by allocate(), so it is added after)
   FillList fl;
-  fl.add(slots, cap, kEmpty64, 1);
   if (one_pass) HM_TRY(allocate(E, E, E, E, n_members, fl));
+  fl.add(slots, cap, kEmpty64, 1);
   if (!E) fl.launch(st);
   if (E) {
     // validate and sort; collapse repeated hyperedges onto first occurrences
@@ -950,7 +1019,8 @@ int build(hm_graph* H, const uint32_t* members_in, const uint64_t* offsets_in, u
     const uint32_t inc_blocks = b34 ? grid_for(b34) : 0;
     k_rows_and_incidence<<<row_blocks + inc_blocks, 256, 0, st>>>(H->bits, uint32_t(N), H->words, H->g2_off,
                                                                   H->g2_adj, row_blocks, H->e3, cur3, H->i3_idx,
-                                                                  H->e4, cur4, H->i4_idx, R, dev_totals);
+                                                                  H->e4, cur4, H->i4_idx, R, H->i3_oth, H->i4_oth,
+                                                                  dev_totals);
     HM_HIP(hipGetLastError());
   } else if (b34) {
     k_inc_fill<<<grid_for(b34), 256, 0, st>>>(H->e3, cur3, H->i3_idx, H->e4, cur4, H->i4_idx, R, dev_totals);
@@ -984,15 +1054,23 @@ int build(hm_graph* H, const uint32_t* members_in, const uint64_t* offsets_in, u
 // work enqueued on that stream so far has run; without, at once (its users
 // have been synchronised).
 void release(hm_graph* H, hipStream_t st = nullptr, bool ordered = false) {
-  void* ps[] = {H->e2,     H->e3,      H->e4,     H->all_members, H->all_off, H->hs2.slot, H->hs3.slot,
-                H->hs4.slot, H->g2_off, H->g2_adj, H->g2_eid,      H->i3_off,  H->i3_idx,   H->i4_off,
-                H->i4_idx, H->bits,     H->hist,   H->sample_hist, H->pl_keys, H->pl_edge,  H->pl_slot, H->pl_codeg, H->pl_third, H->pl_adj, H->pl_pre, H->q_slot, H->q_fourth, H->b4_order, H->hub_rank, H->hub_bits, H->proj_bits, H->ns_tri,
-                H->ns_nbr, H->ns_h3,    H->es,         H->e5,      H->hs5};
-  constexpr size_t n = sizeof(ps) / sizeof(ps[0]);
+  // the arrays the build sizes: one carved block, or one block each
+  void* built[] = {H->e2,     H->e3,     H->e4,     H->all_members, H->all_off, H->hs2.slot, H->hs3.slot,
+                   H->hs4.slot, H->bits, H->i3_oth, H->i4_oth,      H->g2_off,  H->g2_adj,   H->i3_off,
+                   H->i3_idx, H->i4_off, H->i4_idx, H->hist,        H->sample_hist};
+  // and those built later, on first use
+  void* later[] = {H->g2_eid,  H->pl_keys,  H->pl_edge,  H->pl_slot,   H->pl_codeg, H->pl_third, H->pl_adj,
+                   H->pl_pre,  H->q_slot,   H->q_fourth, H->b4_order,  H->hub_rank, H->hub_bits, H->proj_bits,
+                   H->ns_tri,  H->ns_nbr,   H->ns_h3,    H->es,        H->e5,       H->hs5};
+  std::vector<void*> ps(std::begin(later), std::end(later));
+  if (H->arena)
+    ps.push_back(H->arena);
+  else
+    ps.insert(ps.end(), std::begin(built), std::end(built));
   if (ordered) {
-    dfree_on(ps, n, st);
+    dfree_on(ps.data(), ps.size(), st);
   } else {
-    for (size_t i = 0; i < n; ++i) dfree(ps[i]);
+    for (void* p : ps) dfree(p);
   }
   if (H->null_plan) destroy_null_plan(H->null_plan);
   H->null_plan = nullptr;

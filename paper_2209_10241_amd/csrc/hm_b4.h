@@ -17,8 +17,9 @@
 namespace hm {
 
 constexpr uint32_t kMaxWordsB = kBitsetMaxNodes / 32;
-// LDS words one wavefront needs for rows of W words: T_ab, T_ac, T_bc, Q
-__host__ __device__ constexpr uint32_t b4_set_words(uint32_t W) { return 4 * W; }
+// LDS words one wavefront needs for rows of W words: T_ab, T_ac, T_bc, Q and
+// a list of kWave candidate nodes
+__host__ __device__ constexpr uint32_t b4_set_words(uint32_t W) { return 4 * W + kWave; }
 
 __device__ inline void count_class(const uint8_t* lut, unsigned long long* h_main, unsigned long long* h_sub,
                                    uint32_t pattern, uint32_t pair_bits) {
@@ -103,18 +104,19 @@ __device__ void b4_edge_hash(uint32_t a, uint32_t b, uint32_t c, const uint32_t*
 }
 
 // Bit-row version, counting instead of listing.  The wavefront builds, in
-// LDS (sets: 4*W words), bit sets of the nodes v with {a,b,v}, {a,c,v} or
+// LDS (sets: b4_set_words(W) words), bit sets of the nodes v with {a,b,v}, {a,c,v} or
 // {b,c,v} a 3-node hyperedge (T_ab, T_ac, T_bc, from the incident 3-node
 // hyperedges of the two members with the fewest) and with e u {v} a 4-node
-// hyperedge (Q, from those of the member with the fewest).  Any other v leaves e the only hyperedge of size >= 3 in e u {v}, so
-// those v are counted per pairwise combination (av, bv, cv) with popcounts
-// over the rows of a, b, c; each lane classifies the nodes of its words that
-// lie in a T set and outside Q one by one.
+// hyperedge (Q, from those of the member with the fewest).  The incidence
+// entries carry the other members of their hyperedge (others3, others4), so
+// each is one load.  Any other v leaves e the only hyperedge of size >= 3 in
+// e u {v}, so those v are counted per pairwise combination (av, bv, cv) with
+// popcounts over the rows of a, b, c.  The nodes that lie in a T set and
+// outside Q are listed in LDS and classified one per lane.
 template <bool OWN>
-__device__ void b4_edge_bits_count(uint32_t a, uint32_t b, uint32_t c, const uint32_t* __restrict__ e3,
-                                   const uint32_t* __restrict__ e4, const uint32_t* __restrict__ i3_off,
-                                   const uint32_t* __restrict__ i3_idx, const uint32_t* __restrict__ i4_off,
-                                   const uint32_t* __restrict__ i4_idx, const uint32_t* __restrict__ bits,
+__device__ void b4_edge_bits_count(uint32_t a, uint32_t b, uint32_t c, const uint32_t* __restrict__ i3_off,
+                                   const uint32_t* __restrict__ i3_oth, const uint32_t* __restrict__ i4_off,
+                                   const unsigned long long* __restrict__ i4_oth, const uint32_t* __restrict__ bits,
                                    uint32_t W, uint32_t* sets, const uint8_t* lut, unsigned long long* h_main,
                                    unsigned long long* h_sub) {
   const int lane = threadIdx.x & (kWave - 1);
@@ -126,7 +128,6 @@ __device__ void b4_edge_bits_count(uint32_t a, uint32_t b, uint32_t c, const uin
   const uint32_t* Rb = bits + uint64_t(b) * W;
   const uint32_t* Rc = bits + uint64_t(c) * W;
   for (uint32_t w = lane; w < 4 * W; w += kWave) sets[w] = 0;
-  wave_sync();
   // 3-node hyperedges sharing two nodes with e: each holds one of any two
   // members of e, so the lists of the two members with the fewest are read
   // (one found twice sets its bit twice)
@@ -134,28 +135,32 @@ __device__ void b4_edge_bits_count(uint32_t a, uint32_t b, uint32_t c, const uin
   const uint32_t lb0 = i3_off[b], lb = i3_off[b + 1] - lb0;
   const uint32_t lc0 = i3_off[c], lc = i3_off[c + 1] - lc0;
   const bool skip_a = la >= lb && la >= lc, skip_b = !skip_a && lb >= lc;
-  const uint32_t pa = skip_a ? lb0 : la0, l1 = skip_a ? lb : la;
-  const uint32_t pb = (skip_a || skip_b) ? lc0 : lb0, l2 = (skip_a || skip_b) ? lc : lb;
-  for (uint32_t t = lane; t < l1 + l2; t += kWave) {
-    const uint32_t f = i3_idx[t < l1 ? pa + t : pb + (t - l1)];
-    const uint32_t x = e3[3ull * f], y = e3[3ull * f + 1], z = e3[3ull * f + 2];
-    const bool ha = (x == a || y == a || z == a), hb = (x == b || y == b || z == b), hc = (x == c || y == c || z == c);
-    if (int(ha) + int(hb) + int(hc) != 2) continue;
-    const uint32_t v = (x != a && x != b && x != c) ? x : ((y != a && y != b && y != c) ? y : z);
-    uint32_t* T = (ha && hb) ? Tab : (ha ? Tac : Tbc);
-    atomicOr(&T[v >> 5], 1u << (v & 31));
-  }
+  const uint32_t o1 = skip_a ? b : a, pa = skip_a ? lb0 : la0, l1 = skip_a ? lb : la;
+  const uint32_t o2 = (skip_a || skip_b) ? c : b, pb = (skip_a || skip_b) ? lc0 : lb0,
+                 l2 = (skip_a || skip_b) ? lc : lb;
   // 4-node hyperedges containing e, from the shortest list of a member
   const uint32_t fa = i4_off[a + 1] - i4_off[a], fb = i4_off[b + 1] - i4_off[b], fc = i4_off[c + 1] - i4_off[c];
   const uint32_t m4 = (fa <= fb && fa <= fc) ? a : (fb <= fc ? b : c);
   const uint32_t p4 = i4_off[m4], l4 = i4_off[m4 + 1] - p4;
+  wave_sync();
+  for (uint32_t t = lane; t < l1 + l2; t += kWave) {
+    const bool one = t < l1;
+    const uint32_t o = i3_oth[one ? pa + t : pb + (t - l1)];
+    const uint32_t p = one ? o1 : o2;   // the list's node; the hyperedge is {p, y, z}
+    const uint32_t y = o & 0xFFFFu, z = o >> 16;
+    const bool hy = (y == a || y == b || y == c), hz = (z == a || z == b || z == c);
+    if (hy == hz) continue;             // e itself, or only p shared
+    const uint32_t v = hy ? z : y, w = hy ? y : z;   // shared pair {p, w}
+    const bool ha = p == a || w == a, hb = p == b || w == b;
+    uint32_t* T = (ha && hb) ? Tab : (ha ? Tac : Tbc);
+    atomicOr(&T[v >> 5], 1u << (v & 31));
+  }
   for (uint32_t t = lane; t < l4; t += kWave) {
-    const uint32_t f = i4_idx[p4 + t];
-    const uint32_t m0 = e4[4ull * f], m1 = e4[4ull * f + 1], m2 = e4[4ull * f + 2], m3 = e4[4ull * f + 3];
-    const bool i0 = m0 == a || m0 == b || m0 == c, i1 = m1 == a || m1 == b || m1 == c;
-    const bool i2 = m2 == a || m2 == b || m2 == c, i3 = m3 == a || m3 == b || m3 == c;
-    if (int(i0) + int(i1) + int(i2) + int(i3) != 3) continue;
-    const uint32_t v = !i0 ? m0 : (!i1 ? m1 : (!i2 ? m2 : m3));
+    const unsigned long long o = i4_oth[p4 + t];   // the hyperedge is {m4, x, y, z}
+    const uint32_t x = uint32_t(o) & 0xFFFFu, y = uint32_t(o >> 16) & 0xFFFFu, z = uint32_t(o >> 32) & 0xFFFFu;
+    const bool ix = x == a || x == b || x == c, iy = y == a || y == b || y == c, iz = z == a || z == b || z == c;
+    if (int(ix) + int(iy) + int(iz) != 2) continue;
+    const uint32_t v = !ix ? x : (!iy ? y : z);
     atomicOr(&Q[v >> 5], 1u << (v & 31));
   }
   wave_sync();
@@ -163,34 +168,51 @@ __device__ void b4_edge_bits_count(uint32_t a, uint32_t b, uint32_t c, const uin
                  pbc = (Rb[c >> 5] >> (c & 31)) & 1u;
   const uint32_t base_p = pab | (pac << 1) | (pbc << 2) | (1u << 3);
   uint32_t n1 = 0, n2 = 0, n3 = 0, n4 = 0, n5 = 0, n6 = 0, n7 = 0;
-  for (uint32_t w = lane; w < W; w += kWave) {
-    const uint32_t ra = Ra[w], rb = Rb[w], rc = Rc[w];
-    const uint32_t tab_w = Tab[w], tac_w = Tac[w], tbc_w = Tbc[w], q_w = Q[w];
-    uint32_t self = 0;
-    if ((a >> 5) == w) self |= 1u << (a & 31);
-    if ((b >> 5) == w) self |= 1u << (b & 31);
-    if ((c >> 5) == w) self |= 1u << (c & 31);
-    // the ordinary fourth nodes, per combination
-    const uint32_t m = (ra | rb | rc) & ~(tab_w | tac_w | tbc_w | q_w | self);
-    n1 += __popc(m & ra & ~rb & ~rc);
-    n2 += __popc(m & ~ra & rb & ~rc);
-    n3 += __popc(m & ra & rb & ~rc);
-    n4 += __popc(m & ~ra & ~rb & rc);
-    n5 += __popc(m & ra & ~rb & rc);
-    n6 += __popc(m & ~ra & rb & rc);
-    n7 += __popc(m & ra & rb & rc);
-    // the fourth nodes on another 3-node hyperedge (not on a 4-node one)
-    uint32_t cw = (tab_w | tac_w | tbc_w) & ~(q_w | self);
-    while (cw) {
-      const uint32_t vb = __ffs(cw) - 1;
-      cw &= cw - 1;
-      const uint32_t v = (w << 5) | vb;
-      const uint32_t tab = (tab_w >> vb) & 1u, tac = (tac_w >> vb) & 1u, tbc = (tbc_w >> vb) & 1u;
-      if (OWN && ((tab && v < c) || (tac && v < b) || (tbc && v < a))) continue;   // an earlier 3-node hyperedge
-      const uint32_t qa = (ra >> vb) & 1u, qb = (rb >> vb) & 1u, qc = (rc >> vb) & 1u;
-      // local positions a=0, b=1, c=2, v=3
-      const uint32_t pt = base_p | (qa << 4) | (qb << 5) | (tab << 6) | (qc << 7) | (tac << 8) | (tbc << 9);
-      count_class(lut, h_main, h_sub, pt, kPairBits4);
+  uint32_t* list = sets + 4 * W;   // kWave candidate nodes
+  for (uint32_t w0 = 0; w0 < W; w0 += kWave) {
+    const uint32_t w = w0 + lane;
+    uint32_t cw = 0;
+    if (w < W) {
+      const uint32_t ra = Ra[w], rb = Rb[w], rc = Rc[w];
+      const uint32_t tab_w = Tab[w], tac_w = Tac[w], tbc_w = Tbc[w], q_w = Q[w];
+      uint32_t self = 0;
+      if ((a >> 5) == w) self |= 1u << (a & 31);
+      if ((b >> 5) == w) self |= 1u << (b & 31);
+      if ((c >> 5) == w) self |= 1u << (c & 31);
+      // the ordinary fourth nodes, per combination
+      const uint32_t m = (ra | rb | rc) & ~(tab_w | tac_w | tbc_w | q_w | self);
+      n1 += __popc(m & ra & ~rb & ~rc);
+      n2 += __popc(m & ~ra & rb & ~rc);
+      n3 += __popc(m & ra & rb & ~rc);
+      n4 += __popc(m & ~ra & ~rb & rc);
+      n5 += __popc(m & ra & ~rb & rc);
+      n6 += __popc(m & ~ra & rb & rc);
+      n7 += __popc(m & ra & rb & rc);
+      // the fourth nodes on another 3-node hyperedge (not on a 4-node one)
+      cw = (tab_w | tac_w | tbc_w) & ~(q_w | self);
+    }
+    // which are listed in order, kWave at a time, and classified one per lane
+    uint32_t tot;
+    uint32_t at = wave_exclusive_scan(__popc(cw), &tot);
+    for (uint32_t base = 0; base < tot; base += kWave) {
+      while (cw && at < base + kWave) {
+        list[at - base] = (w << 5) | uint32_t(__ffs(cw) - 1);
+        cw &= cw - 1;
+        ++at;
+      }
+      wave_sync();
+      if (base + lane < tot) {
+        const uint32_t v = list[lane], vw = v >> 5, vb = v & 31u;
+        const uint32_t tab = (Tab[vw] >> vb) & 1u, tac = (Tac[vw] >> vb) & 1u, tbc = (Tbc[vw] >> vb) & 1u;
+        // (an earlier 3-node hyperedge inside e u {v} owns it)
+        if (!(OWN && ((tab && v < c) || (tac && v < b) || (tbc && v < a)))) {
+          const uint32_t qa = (Ra[vw] >> vb) & 1u, qb = (Rb[vw] >> vb) & 1u, qc = (Rc[vw] >> vb) & 1u;
+          // local positions a=0, b=1, c=2, v=3
+          const uint32_t pt = base_p | (qa << 4) | (qb << 5) | (tab << 6) | (qc << 7) | (tac << 8) | (tbc << 9);
+          count_class(lut, h_main, h_sub, pt, kPairBits4);
+        }
+      }
+      wave_sync();
     }
   }
   // Reduce over the wavefront (lanes without words hold zeros); a

@@ -77,6 +77,26 @@ __device__ inline bool tri_less(uint32_t a0, uint32_t a1, uint32_t a2, uint32_t 
   if (a1 != b1) return a1 < b1;
   return a2 < b2;
 }
+// The members of a sorted 3- or 4-node hyperedge m other than m[j], 16 bits
+// each in ascending order (node ids below 2^16: graphs with bit rows), kept
+// beside incidence entries so that a walk over a node's list needs no second
+// load for the members.
+static_assert(kBitsetMaxNodes <= 65536, "packed members need node ids below 2^16");
+__device__ inline uint32_t others3(const uint32_t* m, int j) {
+  const uint32_t x = m[j == 0 ? 1 : 0], y = m[j == 2 ? 1 : 2];
+  return x | (y << 16);
+}
+__device__ inline unsigned long long others4(const uint32_t* m, int j) {
+  unsigned long long o = 0;
+  int s = 0;
+  for (int q = 0; q < 4; ++q)
+    if (q != j) {
+      o |= (unsigned long long)m[q] << s;
+      s += 16;
+    }
+  return o;
+}
+
 __device__ inline bool bit_of(const uint32_t* bits, uint32_t words, uint32_t u, uint32_t v) {
   return (bits[uint64_t(u) * words + (v >> 5)] >> (v & 31)) & 1u;
 }

@@ -228,6 +228,9 @@ struct hm_graph {
   uint64_t n_unique = 0;           // unique hyperedges of size >= 2
   uint64_t n_unique_members = 0;   // total members of those
 
+  // one device block holding the arrays the build sizes (from e2 to the
+  // histograms below), when they were carved from it; else each is its own
+  void* arena = nullptr;
   // unique hyperedges per size, ascending tuples, first-occurrence order
   uint32_t* e2 = nullptr;
   uint32_t* e3 = nullptr;
@@ -249,6 +252,10 @@ struct hm_graph {
   // node -> incident 4-node hyperedges (indices into e4)
   uint32_t* i4_off = nullptr;
   uint32_t* i4_idx = nullptr;
+  // with bit rows: beside each incidence entry, the hyperedge's other members
+  // (others3 / others4 of hm_device.h)
+  uint32_t* i3_oth = nullptr;
+  unsigned long long* i4_oth = nullptr;
   // adjacency bit rows of the pairwise graph (n_nodes x words), when kept
   uint32_t* bits = nullptr;
   uint32_t words = 0;

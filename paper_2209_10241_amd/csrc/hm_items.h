@@ -31,6 +31,8 @@ struct View {
   const uint32_t* i3_idx;
   const uint32_t* i4_off;
   const uint32_t* i4_idx;
+  const uint32_t* i3_oth;               // with bit rows: others3 of each i3 entry
+  const unsigned long long* i4_oth;     // with bit rows: others4 of each i4 entry
   Set64 hs2;
   Set128 hs3, hs4;
   const uint32_t* bits;     // n_nodes x W words, or null
@@ -49,6 +51,8 @@ inline View view_of(const hm_graph* H) {
   v.i3_idx = H->i3_idx;
   v.i4_off = H->i4_off;
   v.i4_idx = H->i4_idx;
+  v.i3_oth = H->i3_oth;
+  v.i4_oth = H->i4_oth;
   v.hs2 = H->hs2;
   v.hs3 = H->hs3;
   v.hs4 = H->hs4;
@@ -96,8 +100,7 @@ __device__ inline void b4_item(const View& v, uint64_t i, uint32_t* sets, const 
                                unsigned long long* h_sub) {
   const uint32_t a = v.e3[3 * i], b = v.e3[3 * i + 1], c = v.e3[3 * i + 2];
   if (v.bits)
-    b4_edge_bits_count<true>(a, b, c, v.e3, v.e4, v.i3_off, v.i3_idx, v.i4_off, v.i4_idx, v.bits, v.W, sets, lut,
-                             h_main, h_sub);
+    b4_edge_bits_count<true>(a, b, c, v.i3_off, v.i3_oth, v.i4_off, v.i4_oth, v.bits, v.W, sets, lut, h_main, h_sub);
   else
     b4_edge_hash<true>(a, b, c, v.e3, v.g2_off, v.g2_adj, v.i3_off, v.i3_idx, v.hs2, v.hs3, v.hs4, lut, h_main, h_sub);
 }

@@ -777,13 +777,26 @@ __global__ void k_b_inc_count(uint64_t cap_items, const uint32_t* __restrict__ t
     for (int j = 0; j < J; ++j) atomicAdd(&deg[uint64_t(copyj[q]) * N + e[J * q + j]], 1u);
 }
 
-template <int J>
+// (with bit rows, oth not null: each entry also gets the hyperedge's other
+// members, others3 or others4)
+template <int J, typename O>
 __global__ void k_b_inc_fill(uint64_t cap_items, const uint32_t* __restrict__ total, const uint32_t* __restrict__ e,
-                             const uint32_t* __restrict__ copyj, uint32_t N, uint32_t* cursor, uint32_t* idx) {
+                             const uint32_t* __restrict__ copyj, uint32_t N, uint32_t* cursor, uint32_t* idx,
+                             O* __restrict__ oth) {
   const uint64_t n = *total;
   for (uint64_t q = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; q < n && q < cap_items;
-       q += uint64_t(gridDim.x) * blockDim.x)
-    for (int j = 0; j < J; ++j) idx[atomicAdd(&cursor[uint64_t(copyj[q]) * N + e[J * q + j]], 1u)] = uint32_t(q);
+       q += uint64_t(gridDim.x) * blockDim.x) {
+    uint32_t m[J];
+    for (int j = 0; j < J; ++j) m[j] = e[J * q + j];
+    for (int j = 0; j < J; ++j) {
+      const uint32_t at = atomicAdd(&cursor[uint64_t(copyj[q]) * N + m[j]], 1u);
+      idx[at] = uint32_t(q);
+      if (oth) {
+        if constexpr (J == 3) oth[at] = others3(m, j);
+        else oth[at] = others4(m, j);
+      }
+    }
+  }
 }
 
 __global__ void k_b_bits(uint64_t cap_items, const uint32_t* __restrict__ total, const uint32_t* __restrict__ e2,
@@ -807,6 +820,8 @@ __global__ void k_b_bits(uint64_t cap_items, const uint32_t* __restrict__ total,
 // none is left, so copies of uneven size share the machine.
 struct BatchView {
   const uint32_t *e2, *e3, *e4, *g2_off, *g2_adj, *i3_off, *i3_idx, *i4_off, *i4_idx;
+  const uint32_t* i3_oth;
+  const unsigned long long* i4_oth;
   unsigned long long *hs2, *hs3, *hs4;
   unsigned long long cap2, cap3, cap4;
   const uint32_t* bits;
@@ -825,6 +840,8 @@ __device__ inline View copy_view(const BatchView& b, uint32_t c) {
   v.i3_idx = b.i3_idx;
   v.i4_off = b.i4_off + uint64_t(c) * b.N;
   v.i4_idx = b.i4_idx;
+  v.i3_oth = b.i3_oth;
+  v.i4_oth = b.i4_oth;
   v.hs2 = Set64{b.hs2 + uint64_t(c) * b.cap2, b.cap2 - 1};
   v.hs3 = Set128{b.hs3 + uint64_t(c) * 2 * b.cap3, b.cap3 - 1};
   v.hs4 = Set128{b.hs4 + uint64_t(c) * 2 * b.cap4, b.cap4 - 1};
@@ -1026,6 +1043,8 @@ struct NullPlan {
   uint32_t *deg = nullptr, *cursor = nullptr;
   uint32_t *g2_off = nullptr, *g2_adj = nullptr, *i3_off = nullptr, *i3_idx = nullptr, *i4_off = nullptr,
            *i4_idx = nullptr;
+  uint32_t* i3_oth = nullptr;          // with bit rows
+  unsigned long long* i4_oth = nullptr;
   uint32_t* bits = nullptr;
   unsigned long long* hist_all = nullptr;
   uint32_t *tile_counts = nullptr, *tile_prefix = nullptr, *tile_counter = nullptr;
@@ -1066,6 +1085,8 @@ BatchView batch_view(const NullPlan& P) {
   b.i3_idx = P.i3_idx;
   b.i4_off = P.i4_off;
   b.i4_idx = P.i4_idx;
+  b.i3_oth = P.i3_oth;
+  b.i4_oth = P.i4_oth;
   b.hs2 = P.hs2;
   b.hs3 = P.hs3;
   b.hs4 = P.hs4;
@@ -1171,7 +1192,11 @@ int make_plan(const hm_graph* H, int k, uint32_t R, int model, int sweeps, NullP
   GET(P->i3_idx, 3 * m3);
   GET(P->i4_off, RN + 1);
   GET(P->i4_idx, 4 * m4);
-  if (P->use_bits) GET(P->bits, RN * P->W);
+  if (P->use_bits) {
+    GET(P->bits, RN * P->W);
+    GET(P->i3_oth, 3 * m3);
+    GET(P->i4_oth, 4 * m4);
+  }
   GET(P->hist_all, uint64_t(R) * kNullHistStride);
   GET(P->tile_counts, 3ull * R + 1);
   GET(P->tile_prefix, 3ull * R + 1);
@@ -1272,13 +1297,13 @@ int enqueue_ingest(const hm_graph* H, NullPlan& P, hipStream_t st) {
   HM_HIP(hipGetLastError());
   HM_TRY(scan_u32_ws(P.deg, P.i3_off, RN, P.i3_off + RN, P.scan_ws, st));
   HM_TRY(copy_u32(P.i3_off, P.cursor, RN, st));
-  if (m3) k_b_inc_fill<3><<<grid_for(m3), 256, 0, st>>>(m3, P.tot + 1, P.e3, P.copy3, N, P.cursor, P.i3_idx);
+  if (m3) k_b_inc_fill<3><<<grid_for(m3), 256, 0, st>>>(m3, P.tot + 1, P.e3, P.copy3, N, P.cursor, P.i3_idx, P.i3_oth);
   HM_TRY(fill_u32(P.deg, 0, RN, st));
   if (m4) k_b_inc_count<4><<<grid_for(m4), 256, 0, st>>>(m4, P.tot + 2, P.e4, P.copy4, N, P.deg);
   HM_HIP(hipGetLastError());
   HM_TRY(scan_u32_ws(P.deg, P.i4_off, RN, P.i4_off + RN, P.scan_ws, st));
   HM_TRY(copy_u32(P.i4_off, P.cursor, RN, st));
-  if (m4) k_b_inc_fill<4><<<grid_for(m4), 256, 0, st>>>(m4, P.tot + 2, P.e4, P.copy4, N, P.cursor, P.i4_idx);
+  if (m4) k_b_inc_fill<4><<<grid_for(m4), 256, 0, st>>>(m4, P.tot + 2, P.e4, P.copy4, N, P.cursor, P.i4_idx, P.i4_oth);
   HM_HIP(hipGetLastError());
   if (P.use_bits) {
     HM_TRY(fill_u32(P.bits, 0, RN * P.W, st));

@@ -153,8 +153,8 @@ __device__ void sample_j3_k4(const View& v, const PairLinks& pl, const Queue& q,
     const uint32_t a = v.e3[3 * i], b = v.e3[3 * i + 1], c = v.e3[3 * i + 2];
     unsigned long long* h = (!BITS && rows) ? hw[wv] : row_or(rows, s, h_lds);
     if constexpr (BITS) {
-      b4_edge_bits_count<false>(a, b, c, v.e3, v.e4, v.i3_off, v.i3_idx, v.i4_off, v.i4_idx, v.bits, v.W, sets + wv * b4_set_words(v.W),
-                                lut, h, nullptr);
+      b4_edge_bits_count<false>(a, b, c, v.i3_off, v.i3_oth, v.i4_off, v.i4_oth, v.bits, v.W,
+                                sets + wv * b4_set_words(v.W), lut, h, nullptr);
     } else {
       const B4Ctx x = b4_ctx(v, pl, a, b, c);
       uint32_t n[8];
