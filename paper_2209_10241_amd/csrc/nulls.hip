@@ -413,8 +413,17 @@ __device__ inline bool repeats_node(const uint32_t* m, uint32_t s) {
   return false;
 }
 
+// Round 1's bad hyperedges of a copy are found by k_null_deal in kBadLists
+// lists (hyperedge i in list i % kBadLists, of at most bad_cap entries), each
+// with its own counter kBadStride words from the next, so that few
+// device-scope atomics meet on one address.
+constexpr uint32_t kBadLists = 32;
+constexpr uint32_t kBadStride = 32;
 struct RepairScratch {
-  uint32_t* bad;                 // E
+  uint32_t* bad;                 // bad_stride per repair workgroup
+  uint32_t* counts;              // per copy: kBadLists counters, kBadStride words apart
+  uint32_t bad_cap;              // ceil(E / kBadLists)
+  uint64_t bad_stride;           // kBadLists * bad_cap (>= E)
   uint32_t* chosen;              // 2E padded to a power of two
   unsigned long long* key;       // pool keys, padded
   uint32_t* aux;                 // pool positions
@@ -424,29 +433,78 @@ struct RepairScratch {
   uint64_t pool_pad;             // capacity of the pool arrays (power of two)
 };
 
+// The stub matching dealt per hyperedge, with round 1 of the repair's
+// search: one thread per (copy c, hyperedge i) writes the copy's members of
+// i (the stubs at the sorted positions, as k_null_gather) and, when they
+// repeat a node, lists i among copy c's kBadLists lists at
+// bad + c * bad_stride, in no particular order (a repair round depends only
+// on which hyperedges are bad: the partners are drawn by position in the
+// list and the union is sorted).  Copy c < R has its own repair workgroup.
+__global__ void k_null_deal(uint32_t R, uint32_t E, uint64_t T, const unsigned long long* __restrict__ off,
+                            const uint32_t* __restrict__ vals, const uint32_t* __restrict__ stubs,
+                            uint32_t* __restrict__ members, RepairScratch sc) {
+  const uint64_t n = uint64_t(R) * E;
+  for (uint64_t it = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; it < n; it += uint64_t(gridDim.x) * blockDim.x) {
+    const uint32_t c = uint32_t(it / E), i = uint32_t(it - uint64_t(c) * E);
+    const unsigned long long b = off[i];
+    const uint32_t s = uint32_t(off[i + 1] - b);
+    const uint64_t base = uint64_t(c) * T;
+    uint32_t* m = members + base + b;
+    for (uint32_t j = 0; j < s; ++j) m[j] = stubs[vals[base + b + j] - base];
+    if (repeats_node(m, s)) {
+      const uint64_t list = uint64_t(c) * kBadLists + i % kBadLists;
+      sc.bad[uint64_t(c) * sc.bad_stride + (i % kBadLists) * sc.bad_cap + atomicAdd(&sc.counts[list * kBadStride], 1u)] = i;
+    }
+  }
+}
+
 // One workgroup per copy: repair rounds until no hyperedge repeats a node.
+// pre: k_null_bad has listed round 1's hyperedges (R <= gridDim.x, so the
+// workgroup's copy is its own index).
 __global__ void __launch_bounds__(kThreads) k_null_repair(uint32_t c0, uint32_t R, uint32_t E, uint64_t T,
                                                           const unsigned long long* __restrict__ off,
                                                           uint32_t* __restrict__ members,
                                                           const unsigned long long* __restrict__ seed_p,
-                                                          RepairScratch sc, uint32_t* __restrict__ failed) {
+                                                          RepairScratch sc, bool pre, uint32_t* __restrict__ failed) {
   __shared__ uint32_t wsum[kWavesPerBlock];
+  __shared__ uint32_t lstart[kBadLists + 1];
   __shared__ unsigned long long lk[kLdsBitonic];
   __shared__ uint32_t la[kLdsBitonic], lv[kLdsBitonic];
   const unsigned long long seed = *seed_p;
   for (uint32_t c = blockIdx.x; c < R; c += gridDim.x) {
     uint32_t* m = members + uint64_t(c) * T;
-    uint32_t* bad = sc.bad + uint64_t(blockIdx.x) * E;
+    uint32_t* bad = sc.bad + uint64_t(blockIdx.x) * sc.bad_stride;
     uint32_t* chosen = sc.chosen + uint64_t(blockIdx.x) * sc.chosen_pad;
     unsigned long long* key = sc.key + uint64_t(blockIdx.x) * sc.pool_pad;
     uint32_t* aux = sc.aux + uint64_t(blockIdx.x) * sc.pool_pad;
     uint32_t* val = sc.val + uint64_t(blockIdx.x) * sc.pool_pad;
     uint32_t* poff = sc.off + uint64_t(blockIdx.x) * sc.chosen_pad;
     const unsigned long long k1 = (kDomainNull << 32) | (c0 + c);
-    // round 1 looks at every hyperedge; later rounds only at the last pool
-    uint32_t n_bad = block_compact(E, [&](uint32_t i) {
-      return repeats_node(m + off[i], uint32_t(off[i + 1] - off[i]));
-    }, bad, wsum);
+    // round 1 looks at every hyperedge (pre: k_null_deal did, into lists
+    // that are joined here through chosen); later rounds only at the last pool
+    uint32_t n_bad = 0;
+    if (pre) {
+      if (threadIdx.x == 0) {
+        uint32_t at = 0;
+        for (uint32_t k = 0; k < kBadLists; ++k) {
+          lstart[k] = at;
+          at += sc.counts[(uint64_t(c) * kBadLists + k) * kBadStride];
+        }
+        lstart[kBadLists] = at;
+      }
+      __syncthreads();
+      n_bad = lstart[kBadLists];
+      for (uint32_t k = threadIdx.x / kWave; k < kBadLists; k += kWavesPerBlock)
+        for (uint32_t j = lstart[k] + (threadIdx.x & (kWave - 1)); j < lstart[k + 1]; j += kWave)
+          chosen[j] = bad[k * sc.bad_cap + (j - lstart[k])];
+      __syncthreads();
+      for (uint32_t q = threadIdx.x; q < n_bad; q += kThreads) bad[q] = chosen[q];
+      __syncthreads();
+    } else {
+      n_bad = block_compact(E, [&](uint32_t i) {
+        return repeats_node(m + off[i], uint32_t(off[i + 1] - off[i]));
+      }, bad, wsum);
+    }
     int r = 1;
     for (; n_bad > 0 && r <= kMaxRepairRounds; ++r) {
       // partners, then the ascending union of bad and partners
@@ -1151,7 +1209,10 @@ int make_plan(const hm_graph* H, int k, uint32_t R, int model, int sweeps, NullP
   P->repair_blocks = R < 256 ? R : 256;
   P->rs.chosen_pad = pow2_at_least(2ull * P->E + 2);
   P->rs.pool_pad = pow2_at_least(P->T + 1);
-  GET(P->rs.bad, uint64_t(P->repair_blocks) * P->E + 1);
+  P->rs.bad_cap = (P->E + kBadLists - 1) / kBadLists;
+  P->rs.bad_stride = uint64_t(kBadLists) * P->rs.bad_cap;
+  GET(P->rs.bad, uint64_t(P->repair_blocks) * P->rs.bad_stride + 1);
+  GET(P->rs.counts, uint64_t(P->repair_blocks) * kBadLists * kBadStride);
   GET(P->rs.chosen, uint64_t(P->repair_blocks) * P->rs.chosen_pad);
   GET(P->rs.off, uint64_t(P->repair_blocks) * P->rs.chosen_pad);
   GET(P->rs.key, uint64_t(P->repair_blocks) * P->rs.pool_pad);
@@ -1228,10 +1289,17 @@ int enqueue_stubs(const hm_graph* H, NullPlan& P, uint32_t c0, hipStream_t st) {
   const uint64_t n = uint64_t(P.R) * P.T;
   if (n == 0) return HM_OK;
   HM_TRY(enqueue_order(P, n, P.T, 0, kDomainNull, c0, st));
-  k_null_gather<<<grid_for(n), 256, 0, st>>>(P.svals, n, P.T, H->all_members, P.members);
-  HM_HIP(hipGetLastError());
   HM_TRY(fill_u32(P.failed, 0, 1, st));
-  k_null_repair<<<P.repair_blocks, kThreads, 0, st>>>(c0, P.R, P.E, P.T, H->all_off, P.members, P.seed, P.rs,
+  const bool pre = P.R <= P.repair_blocks;
+  if (pre) {
+    HM_TRY(fill_u32(P.rs.counts, 0, uint64_t(P.R) * kBadLists * kBadStride, st));
+    k_null_deal<<<grid_for(uint64_t(P.R) * P.E), 256, 0, st>>>(P.R, P.E, P.T, H->all_off, P.svals, H->all_members,
+                                                                P.members, P.rs);
+  } else {
+    k_null_gather<<<grid_for(n), 256, 0, st>>>(P.svals, n, P.T, H->all_members, P.members);
+  }
+  HM_HIP(hipGetLastError());
+  k_null_repair<<<P.repair_blocks, kThreads, 0, st>>>(c0, P.R, P.E, P.T, H->all_off, P.members, P.seed, P.rs, pre,
                                                       P.failed);
   HM_HIP(hipGetLastError());
   return HM_OK;
@@ -1443,7 +1511,10 @@ int null_copies(const hm_graph* H, uint32_t c0, uint32_t R, uint64_t seed, uint3
   P.repair_blocks = R < 256 ? R : 256;
   P.rs.chosen_pad = pow2_at_least(2ull * P.E + 2);
   P.rs.pool_pad = pow2_at_least(P.T + 1);
-  HM_TRY(P.get(&P.rs.bad, uint64_t(P.repair_blocks) * P.E + 1));
+  P.rs.bad_cap = (P.E + kBadLists - 1) / kBadLists;
+  P.rs.bad_stride = uint64_t(kBadLists) * P.rs.bad_cap;
+  HM_TRY(P.get(&P.rs.bad, uint64_t(P.repair_blocks) * P.rs.bad_stride + 1));
+  HM_TRY(P.get(&P.rs.counts, uint64_t(P.repair_blocks) * kBadLists * kBadStride));
   HM_TRY(P.get(&P.rs.chosen, uint64_t(P.repair_blocks) * P.rs.chosen_pad));
   HM_TRY(P.get(&P.rs.off, uint64_t(P.repair_blocks) * P.rs.chosen_pad));
   HM_TRY(P.get(&P.rs.key, uint64_t(P.repair_blocks) * P.rs.pool_pad));
