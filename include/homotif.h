@@ -370,7 +370,10 @@ int hm_stratum_search(const hm_graph* H, int k, uint64_t S, const double* ratio3
 int hm_profile_quality(const double* est, const double* exact, int n_classes, double* out3, void* stream);
 
 /* Items per tile chosen for the last count_nulls on H (host array of 3:
- * 3-node hyperedges, pairs, hyperedges of size k); HM_EINVAL before any. */
+ * 3-node hyperedges, pairs, hyperedges of size k); HM_EINVAL before any.  A
+ * tile is taken by one wavefront, or, at order 4 when a copy's adjacency bit
+ * rows and row starts fit in 48 KB of LDS, by one workgroup whose four
+ * wavefronts share its items. */
 int hm_null_tile_sizes(const hm_graph* H, uint32_t* out3);
 
 /* Null copy `copy` of count_nulls' model (host outputs): members in the

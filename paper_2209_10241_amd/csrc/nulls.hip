@@ -586,19 +586,28 @@ __global__ void __launch_bounds__(kThreads) k_null_repair(uint32_t c0, uint32_t 
   }
 }
 
-// z_m over the R copies, fp64, rounded to fp32
-__global__ void k_zscore(const int64_t* __restrict__ real, const int64_t* __restrict__ nulls, uint32_t R,
-                         int n_classes, float* __restrict__ z) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= n_classes) return;
+__device__ inline double wave_sum_f64(double x) {
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) x += __shfl_xor(x, o, kWave);
+  return x;
+}
+
+// z_m over the R copies, fp64, rounded to fp32: one wavefront per class m
+// (blockIdx.x), its lanes taking the copies in turn
+__global__ void __launch_bounds__(kWave) k_zscore(const int64_t* __restrict__ real, const int64_t* __restrict__ nulls,
+                                                  uint32_t R, int n_classes, float* __restrict__ z) {
+  const int c = blockIdx.x;
+  const uint32_t lane = threadIdx.x;
   double s = 0.0;
-  for (uint32_t i = 0; i < R; ++i) s += double(nulls[uint64_t(i) * n_classes + c]);
-  const double mean = s / double(R);
+  for (uint32_t i = lane; i < R; i += kWave) s += double(nulls[uint64_t(i) * n_classes + c]);
+  const double mean = wave_sum_f64(s) / double(R);
   double ss = 0.0;
-  for (uint32_t i = 0; i < R; ++i) {
+  for (uint32_t i = lane; i < R; i += kWave) {
     const double d = double(nulls[uint64_t(i) * n_classes + c]) - mean;
     ss += d * d;
   }
+  ss = wave_sum_f64(ss);
+  if (lane != 0) return;
   const double sd = sqrt(ss / double(R - 1));
   const double x = double(real[c]);
   double out;
@@ -1049,6 +1058,121 @@ __global__ void __launch_bounds__(kThreads) k_null_count(BatchView b, uint32_t R
   }
 }
 
+// Order 4 with bit rows, a copy's bit matrix and row starts small enough for
+// LDS (null_lds_bytes): a workgroup takes a tile at a time, copies the bit
+// matrix and the row starts of the tile's copy into LDS when the copy
+// changes, and its wavefronts share the tile's items (every wavefront the
+// next of every kWavesPerBlock items; phase 2 one item per thread).  The
+// items then read adjacency words and row bounds from LDS rather than L2,
+// as the single-graph count does.  Dynamic LDS: the wavefronts' b4 sets,
+// then the rows (16-byte aligned) and the three row-start arrays.
+__host__ __device__ inline size_t null_lds_table_words(uint32_t N, uint32_t W) {
+  return size_t(N) * W + 3 * (size_t(N) + 1);
+}
+__global__ void __launch_bounds__(kThreads) k_null_count_lds(BatchView b, uint32_t R,
+                                                             const uint32_t* __restrict__ tile_prefix,
+                                                             uint32_t* __restrict__ counter, Chunks ch,
+                                                             const uint8_t* __restrict__ lut_g,
+                                                             unsigned long long* __restrict__ hist_all) {
+  __shared__ uint8_t lut[2048];
+  __shared__ unsigned long long wh[kWavesPerBlock][512];
+  extern __shared__ uint32_t dyn_lds[];
+  __shared__ uint32_t ylist[kWavesPerBlock][kWave];
+  __shared__ uint32_t s_tile;
+  load_lut(lut, lut_g, 2048);
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wv = threadIdx.x / kWave;
+  unsigned long long* h_main = wh[wv];
+  unsigned long long* h_sub = wh[wv] + 256;
+  uint32_t* sets = dyn_lds + wv * b4_set_words(b.W);
+  uint32_t* rows = dyn_lds + kWavesPerBlock * b4_set_words(b.W);
+  const uint32_t nw = b.N * b.W;
+  uint32_t* offs = rows + nw;
+  const uint32_t total = tile_prefix[3 * R];
+  const C4Lanes L = c4_lanes(b.W);
+  const bool id = batch_ident(b, 4);
+  uint32_t loaded = 0xFFFFFFFFu;
+  while (true) {
+    __syncthreads();   // the previous tile is done with s_tile and the LDS tables
+    if (threadIdx.x == 0) s_tile = atomicAdd(counter, 1u);
+    __syncthreads();
+    const uint32_t t = s_tile;
+    if (t >= total) break;
+    // the slot (phase, copy) whose tile range holds t
+    uint32_t lo = 0, hi = 3 * R;
+    while (hi - lo > 1) {
+      const uint32_t mid = (lo + hi) >> 1;
+      if (tile_prefix[mid] <= t) lo = mid; else hi = mid;
+    }
+    const uint32_t ph = lo / R, c = lo % R;
+    const uint32_t first = (t - tile_prefix[lo]) * ch.per_tile[ph];
+    View v = copy_view(b, c);
+    if (c != loaded) {
+      const uint4* src = reinterpret_cast<const uint4*>(v.bits);
+      uint4* dst = reinterpret_cast<uint4*>(rows);
+      for (uint32_t i = threadIdx.x; i < nw / 4; i += kThreads) dst[i] = src[i];
+      for (uint32_t i = 4 * (nw / 4) + threadIdx.x; i < nw; i += kThreads) rows[i] = v.bits[i];
+      for (uint32_t i = threadIdx.x; i <= b.N; i += kThreads) {
+        offs[i] = v.g2_off[i];
+        offs[b.N + 1 + i] = v.i3_off[i];
+        offs[2 * (b.N + 1) + i] = v.i4_off[i];
+      }
+      loaded = c;
+      __syncthreads();
+    }
+    v.bits = rows;
+    v.g2_off = offs;
+    v.i3_off = offs + b.N + 1;
+    v.i4_off = offs + 2 * (b.N + 1);
+    unsigned long long* hc = hist_all + uint64_t(c) * kNullHistStride;
+    for (uint32_t i = lane; i < 512; i += kWave) wh[wv][i] = 0;
+    wave_sync();
+    if (ph == 0) {
+      const uint32_t n = b.base3[c + 1] - b.base3[c];
+      const uint32_t last = min(n, first + ch.per_tile[0]);
+      for (uint32_t j = first + wv; j < last; j += kWavesPerBlock) b4_item(v, b.base3[c] + j, sets, lut, h_main, h_sub);
+    } else if (ph == 1) {
+      const uint32_t n2c = b.base2[c + 1] - b.base2[c];
+      const uint32_t n = n2c + (id ? b.N : 0u);
+      const uint32_t last = min(n, first + ch.per_tile[1]);
+      if (id) {
+        IdAcc acc;
+        id_zero(acc);
+        for (uint32_t j = first + wv; j < last; j += kWavesPerBlock) {
+          if (j < n2c) {
+            const uint64_t q = b.base2[c] + j;
+            id_edge_item(v, b.e2[2 * q], b.e2[2 * q + 1], L, ylist[wv], acc);
+          } else {
+            id_node_item(v, j - n2c, acc);
+          }
+        }
+        id_flush(acc, hc + kIdAcc);
+      } else {
+        C4Acc acc;
+        c4_zero(acc);
+        for (uint32_t j = first + wv; j < last; j += kWavesPerBlock) {
+          const uint64_t q = b.base2[c] + j;
+          c4_bits_item(v, b.e2[2 * q], b.e2[2 * q + 1], L, ylist[wv], acc, lut, hc + kG2);
+        }
+        c4_flush(acc, lut, hc + kG2);
+      }
+    } else {
+      const uint32_t n = b.base4[c + 1] - b.base4[c];
+      const uint32_t last = min(n, first + ch.per_tile[2]);
+      for (uint32_t j = first + threadIdx.x; j < last; j += kThreads) {
+        const uint64_t q = b.base4[c] + j;
+        count_class(lut, h_main, h_sub, a4_pattern(v, b.e4[4 * q], b.e4[4 * q + 1], b.e4[4 * q + 2], b.e4[4 * q + 3]),
+                    kPairBits4);
+      }
+    }
+    wave_sync();
+    for (uint32_t i = lane; i < 512; i += kWave) {
+      const unsigned long long x = wh[wv][i];
+      if (x) atomicAdd(hc + i, x);   // kMain = 0, kSub = 256
+    }
+  }
+}
+
 struct ClassMaskB {
   unsigned long long w[4];
 };
@@ -1391,6 +1515,38 @@ unsigned persistent_grid(size_t lds) {
   return unsigned(cus > 0 ? cus : 256) * unsigned(per_cu);
 }
 
+// Workgroups of k_null_count_lds resident at once, at most four per CU: the
+// register and wave limits from the occupancy query without LDS, the LDS
+// limit from the CU's LDS size (static plus `lds` dynamic bytes per
+// workgroup).  More workgroups than fit only wait for the first to finish:
+// the count claims its tiles until none is left.
+unsigned persistent_grid_lds(size_t lds) {
+  int dev = 0, cus = 256, per_cu = 1, lds_cu = 0;
+  if (hipGetDevice(&dev) == hipSuccess) {
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    (void)hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev);
+  }
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_null_count_lds, kThreads, 0) != hipSuccess) per_cu = 1;
+  hipFuncAttributes attr{};
+  size_t per_wg = lds;
+  if (hipFuncGetAttributes(&attr, reinterpret_cast<const void*>(k_null_count_lds)) == hipSuccess)
+    per_wg += attr.sharedSizeBytes;
+  (void)hipGetLastError();
+  if (lds_cu > 0 && per_wg > 0) per_cu = std::min<int>(per_cu, int(size_t(lds_cu) / per_wg));
+  per_cu = per_cu < 1 ? 1 : (per_cu > 4 ? 4 : per_cu);
+  return unsigned(cus > 0 ? cus : 256) * unsigned(per_cu);
+}
+
+// Whether the batch counts with k_null_count_lds (order 4, bit rows, a copy's
+// tables in at most kNullLdsMaxBytes), and its dynamic LDS.
+constexpr size_t kNullLdsMaxBytes = 48 * 1024;
+bool null_lds(const NullPlan& P) {
+  return P.k == 4 && P.use_bits && null_lds_table_words(P.N, P.W) * 4 <= kNullLdsMaxBytes;
+}
+size_t null_lds_bytes(const NullPlan& P) {
+  return (size_t(kWavesPerBlock) * b4_set_words(P.W) + null_lds_table_words(P.N, P.W)) * 4;
+}
+
 int enqueue_count(const hm_graph* H, NullPlan& P, const Chunks& ch, hipStream_t st) {
   const uint8_t *lut4 = nullptr, *lut3 = nullptr;
   HM_TRY(device_luts(H->device, &lut4, &lut3));
@@ -1401,9 +1557,15 @@ int enqueue_count(const hm_graph* H, NullPlan& P, const Chunks& ch, hipStream_t 
   HM_TRY(scan_u32_ws(P.tile_counts, P.tile_prefix, 3ull * R, P.tile_prefix + 3ull * R, P.scan_ws, st));
   HM_TRY(fill_u64(P.hist_all, 0, uint64_t(R) * kNullHistStride, st));
   HM_TRY(fill_u32(P.tile_counter, 0, 1, st));
-  const size_t lds = (P.k == 4 && bv.bits) ? size_t(kWavesPerBlock) * b4_set_words(bv.W) * 4 : 0;
-  k_null_count<<<persistent_grid(lds), kThreads, lds, st>>>(bv, R, P.k, P.tile_prefix, P.tile_counter, ch,
-                                                       P.k == 4 ? lut4 : lut3, P.hist_all);
+  if (null_lds(P)) {
+    const size_t lds = null_lds_bytes(P);
+    k_null_count_lds<<<persistent_grid_lds(lds), kThreads, lds, st>>>(bv, R, P.tile_prefix, P.tile_counter, ch, lut4,
+                                                                      P.hist_all);
+  } else {
+    const size_t lds = (P.k == 4 && bv.bits) ? size_t(kWavesPerBlock) * b4_set_words(bv.W) * 4 : 0;
+    k_null_count<<<persistent_grid(lds), kThreads, lds, st>>>(bv, R, P.k, P.tile_prefix, P.tile_counter, ch,
+                                                         P.k == 4 ? lut4 : lut3, P.hist_all);
+  }
   HM_HIP(hipGetLastError());
   const ClassTables& t = class_tables();
   ClassMaskB pairs_only{{0, 0, 0, 0}};
@@ -1426,7 +1588,7 @@ int enqueue_all(const hm_graph* H, NullPlan& P, hipStream_t st) {
   HM_TRY(enqueue_ingest(H, P, st));
   HM_TRY(enqueue_count(H, P, P.chunks, st));
   const int C = class_tables().n_classes[P.k];
-  k_zscore<<<1, 256, 0, st>>>(P.real, P.nulls, P.R, C, P.z);
+  k_zscore<<<C, kWave, 0, st>>>(P.real, P.nulls, P.R, C, P.z);
   HM_HIP(hipGetLastError());
   return HM_OK;
 }
@@ -1449,15 +1611,20 @@ int autotune(const hm_graph* H, NullPlan& P, hipStream_t st) {
       return HM_OK;
     }
   }
-  static const uint32_t cand_b[] = {1, 2, 4, 8, 16};
-  static const uint32_t cand_c[] = {1, 2, 4, 8, 16};
+  // items per tile: per wavefront, or with k_null_count_lds per workgroup
+  // (its kWavesPerBlock wavefronts share a tile)
+  static const uint32_t cand_wave[] = {1, 2, 4, 8, 16};
+  static const uint32_t cand_block[] = {16, 32, 64, 128, 256};
+  const uint32_t* cand_b = null_lds(P) ? cand_block : cand_wave;
+  const uint32_t* cand_c = cand_b;
   hipEvent_t e0, e1;
   HM_HIP(hipEventCreate(&e0));
   HM_HIP(hipEventCreate(&e1));
   float best = 1e30f;
   Chunks best_ch = P.chunks;
-  for (uint32_t cb : cand_b)
-    for (uint32_t cc : cand_c) {
+  for (int ib = 0; ib < 5; ++ib)
+    for (int ic = 0; ic < 5; ++ic) {
+      const uint32_t cb = cand_b[ib], cc = cand_c[ic];
       Chunks ch{{cb, cc, P.k == 4 ? 256u : 1024u}};
       if (P.k == 3) ch.per_tile[1] = 64 * cc;
       float total = 0.f;
