@@ -17,6 +17,7 @@
 namespace hm {
 
 constexpr uint32_t kMaxWordsB = kBitsetMaxNodes / 32;
+constexpr int kB4Batch = 4;   // incidence entries a lane loads at once
 // LDS words one wavefront needs for rows of W words: T_ab, T_ac, T_bc, Q and
 // a list of kWave candidate nodes
 __host__ __device__ constexpr uint32_t b4_set_words(uint32_t W) { return 4 * W + kWave; }
@@ -143,25 +144,42 @@ __device__ void b4_edge_bits_count(uint32_t a, uint32_t b, uint32_t c, const uin
   const uint32_t m4 = (fa <= fb && fa <= fc) ? a : (fb <= fc ? b : c);
   const uint32_t p4 = i4_off[m4], l4 = i4_off[m4 + 1] - p4;
   wave_sync();
-  for (uint32_t t = lane; t < l1 + l2; t += kWave) {
-    const bool one = t < l1;
-    const uint32_t o = i3_oth[one ? pa + t : pb + (t - l1)];
-    const uint32_t p = one ? o1 : o2;   // the list's node; the hyperedge is {p, y, z}
-    const uint32_t y = o & 0xFFFFu, z = o >> 16;
-    const bool hy = (y == a || y == b || y == c), hz = (z == a || z == b || z == c);
-    if (hy == hz) continue;             // e itself, or only p shared
-    const uint32_t v = hy ? z : y, w = hy ? y : z;   // shared pair {p, w}
-    const bool ha = p == a || w == a, hb = p == b || w == b;
-    uint32_t* T = (ha && hb) ? Tab : (ha ? Tac : Tbc);
-    atomicOr(&T[v >> 5], 1u << (v & 31));
-  }
-  for (uint32_t t = lane; t < l4; t += kWave) {
-    const unsigned long long o = i4_oth[p4 + t];   // the hyperedge is {m4, x, y, z}
-    const uint32_t x = uint32_t(o) & 0xFFFFu, y = uint32_t(o >> 16) & 0xFFFFu, z = uint32_t(o >> 32) & 0xFFFFu;
-    const bool ix = x == a || x == b || x == c, iy = y == a || y == b || y == c, iz = z == a || z == b || z == c;
-    if (int(ix) + int(iy) + int(iz) != 2) continue;
-    const uint32_t v = !ix ? x : (!iy ? y : z);
-    atomicOr(&Q[v >> 5], 1u << (v & 31));
+  // the entries of both walks are loaded kB4Batch per lane at a time before
+  // any is used, so that their latencies overlap
+  // (batch q: 3-node entries [q * kB4Batch * kWave, (q + 1) * kB4Batch * kWave),
+  // 4-node entries [q * kWave, (q + 1) * kWave))
+  const uint32_t l3 = l1 + l2;
+  for (uint32_t q = 0; q * (kB4Batch * kWave) < l3 || q * kWave < l4; ++q) {
+    const uint32_t t0 = q * (kB4Batch * kWave);
+    uint32_t o3[kB4Batch];
+#pragma unroll
+    for (int u = 0; u < kB4Batch; ++u) {
+      const uint32_t t = t0 + u * kWave + lane;
+      o3[u] = t < l3 ? i3_oth[t < l1 ? pa + t : pb + (t - l1)] : 0u;
+    }
+    const uint32_t t4 = q * kWave + lane;
+    const unsigned long long o4 = t4 < l4 ? i4_oth[p4 + t4] : 0ull;
+#pragma unroll
+    for (int u = 0; u < kB4Batch; ++u) {
+      const uint32_t t = t0 + u * kWave + lane;
+      if (t >= l3) continue;
+      const uint32_t p = t < l1 ? o1 : o2;   // the list's node; the hyperedge is {p, y, z}
+      const uint32_t y = o3[u] & 0xFFFFu, z = o3[u] >> 16;
+      const bool hy = (y == a || y == b || y == c), hz = (z == a || z == b || z == c);
+      if (hy == hz) continue;                // e itself, or only p shared
+      const uint32_t v = hy ? z : y, w = hy ? y : z;   // shared pair {p, w}
+      const bool ha = p == a || w == a, hb = p == b || w == b;
+      uint32_t* T = (ha && hb) ? Tab : (ha ? Tac : Tbc);
+      atomicOr(&T[v >> 5], 1u << (v & 31));
+    }
+    if (t4 < l4) {   // the hyperedge is {m4, x, y, z}
+      const uint32_t x = uint32_t(o4) & 0xFFFFu, y = uint32_t(o4 >> 16) & 0xFFFFu, z = uint32_t(o4 >> 32) & 0xFFFFu;
+      const bool ix = x == a || x == b || x == c, iy = y == a || y == b || y == c, iz = z == a || z == b || z == c;
+      if (int(ix) + int(iy) + int(iz) == 2) {
+        const uint32_t v = !ix ? x : (!iy ? y : z);
+        atomicOr(&Q[v >> 5], 1u << (v & 31));
+      }
+    }
   }
   wave_sync();
   const uint32_t pab = (Ra[b >> 5] >> (b & 31)) & 1u, pac = (Ra[c >> 5] >> (c & 31)) & 1u,
