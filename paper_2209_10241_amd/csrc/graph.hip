@@ -32,10 +32,27 @@ struct DevFlags {
 };
 
 constexpr int kRegSort = 16;
+constexpr uint32_t kNetSort = 8;   // hyperedges up to this size: loaded at once, sorted by a network
 
+// Batcher's odd-even merge sorting network for 8 values (19 comparators).
+__device__ inline void sort8(uint32_t* r) {
+  constexpr int kNet[19][2] = {{0, 2}, {1, 3}, {4, 6}, {5, 7}, {0, 4}, {1, 5}, {2, 6}, {3, 7}, {0, 1}, {2, 3},
+                               {4, 5}, {6, 7}, {2, 4}, {3, 5}, {1, 4}, {3, 6}, {1, 2}, {3, 4}, {5, 6}};
+#pragma unroll
+  for (int q = 0; q < 19; ++q) {
+    const uint32_t x = r[kNet[q][0]], y = r[kNet[q][1]];
+    r[kNet[q][0]] = min(x, y);
+    r[kNet[q][1]] = max(x, y);
+  }
+}
+
+__device__ inline unsigned long long tuple_hash_start(uint32_t s) { return mix64(0x51ed270b27a3ffb1ull ^ s); }
+__device__ inline unsigned long long tuple_hash_step(unsigned long long h, uint32_t x, uint32_t i) {
+  return mix64(h ^ (x + 0x9e3779b97f4a7c15ull * (i + 1)));
+}
 __device__ inline unsigned long long tuple_hash(const uint32_t* m, uint32_t s) {
-  unsigned long long h = mix64(0x51ed270b27a3ffb1ull ^ s);
-  for (uint32_t i = 0; i < s; ++i) h = mix64(h ^ (m[i] + 0x9e3779b97f4a7c15ull * (i + 1)));
+  unsigned long long h = tuple_hash_start(s);
+  for (uint32_t i = 0; i < s; ++i) h = tuple_hash_step(h, m[i], i);
   return h;
 }
 
@@ -85,7 +102,28 @@ __global__ void k_prepare(const uint32_t* __restrict__ members, const uint64_t* 
       const uint32_t s = s64 > 0xFFFFFFFFull ? 0xFFFFFFFFu : uint32_t(s64);
       if (s == 0) err |= kErrEmpty;
       uint32_t* out = sm + b;
-      if (s <= kRegSort) {
+      unsigned long long h = 0;
+      if (s <= kNetSort) {
+        // every member load in flight at once; the padding (above any node
+        // id) sorts last
+        uint32_t r[kNetSort];
+#pragma unroll
+        for (uint32_t j = 0; j < kNetSort; ++j) r[j] = j < s ? members[b + j] : 0xFFFFFFFFu;
+#pragma unroll
+        for (uint32_t j = 0; j < kNetSort; ++j)
+          if (j < s && r[j] >= n_nodes) err |= kErrBadId;
+        sort8(r);
+#pragma unroll
+        for (uint32_t j = 0; j < kNetSort; ++j)
+          if (j < s) out[j] = r[j];
+#pragma unroll
+        for (uint32_t j = 1; j < kNetSort; ++j)
+          if (j < s && r[j] == r[j - 1]) err |= kErrRepeat;
+        h = tuple_hash_start(s);
+#pragma unroll
+        for (uint32_t j = 0; j < kNetSort; ++j)
+          if (j < s) h = tuple_hash_step(h, r[j], j);
+      } else if (s <= kRegSort) {
         uint32_t r[kRegSort];
         for (uint32_t j = 0; j < s; ++j) {
           uint32_t v = members[b + j];
@@ -110,10 +148,13 @@ __global__ void k_prepare(const uint32_t* __restrict__ members, const uint64_t* 
           out[k] = v;
         }
       }
-      for (uint32_t j = 1; j < s; ++j)
-        if (out[j] == out[j - 1]) err |= kErrRepeat;
+      if (s > kNetSort) {
+        for (uint32_t j = 1; j < s; ++j)
+          if (out[j] == out[j - 1]) err |= kErrRepeat;
+        h = tuple_hash(out, s);
+      }
       size[i] = s;
-      hash[i] = tuple_hash(out, s);
+      hash[i] = h;
     }
     ecode[i] = uint8_t(err);
   }
@@ -460,11 +501,19 @@ __global__ void __launch_bounds__(kTile) k_gather_tiles(const uint32_t* __restri
     pos[k] = p;
   }
   const uint32_t* m = sm + off[i];
-  for (uint32_t j = 0; j < s; ++j) g.all_members[pos[4] + j] = m[j];
+  // the first four members, loaded at once (the rest of a larger hyperedge
+  // one by one)
+  uint32_t mm[4];
+#pragma unroll
+  for (uint32_t j = 0; j < 4; ++j) mm[j] = j < s ? m[j] : 0u;
+#pragma unroll
+  for (uint32_t j = 0; j < 4; ++j)
+    if (j < s) g.all_members[pos[4] + j] = mm[j];
+  for (uint32_t j = 4; j < s; ++j) g.all_members[pos[4] + j] = m[j];
   g.all_off[pos[0]] = pos[4];
   if (pos[0] + 1 == total[0]) g.all_off[total[0]] = total[4];
   if (s == 2) {
-    const uint32_t a = m[0], b = m[1];
+    const uint32_t a = mm[0], b = mm[1];
     g.e2[2 * pos[1]] = a;
     g.e2[2 * pos[1] + 1] = b;
     const unsigned long long key = key2(a, b);
@@ -479,15 +528,19 @@ __global__ void __launch_bounds__(kTile) k_gather_tiles(const uint32_t* __restri
     atomicAdd(&g.deg2[uint64_t(b) * g.R + cp], 1u);
   } else if (s == 3 || s == 4) {
     uint32_t* e = s == 3 ? g.e3 + 3 * pos[2] : g.e4 + 4 * pos[3];
-    for (uint32_t j = 0; j < s; ++j) e[j] = m[j];
-    const Key128 key = s == 3 ? key3(m[0], m[1], m[2]) : key4(m[0], m[1], m[2], m[3]);
+#pragma unroll
+    for (uint32_t j = 0; j < 4; ++j)
+      if (j < s) e[j] = mm[j];
+    const Key128 key = s == 3 ? key3(mm[0], mm[1], mm[2]) : key4(mm[0], mm[1], mm[2], mm[3]);
     const Set128& set = s == 3 ? g.hs3 : g.hs4;
     unsigned long long h = hash128(key) & set.mask;
     while (atomicCAS(set.slot + 2 * h, kEmpty64, key.hi) != kEmpty64) h = (h + 1) & set.mask;
     set.slot[2 * h + 1] = key.lo;
     uint32_t* deg = s == 3 ? g.deg3 : g.deg4;
     const uint32_t cp = uint32_t(s == 3 ? pos[2] : pos[3]) & (g.R - 1);
-    for (uint32_t j = 0; j < s; ++j) atomicAdd(&deg[uint64_t(m[j]) * g.R + cp], 1u);
+#pragma unroll
+    for (uint32_t j = 0; j < 4; ++j)
+      if (j < s) atomicAdd(&deg[uint64_t(mm[j]) * g.R + cp], 1u);
   }
 }
 
@@ -496,6 +549,9 @@ __global__ void __launch_bounds__(kTile) k_gather_tiles(const uint32_t* __restri
 // fill cursors c of every (node, copy).  One workgroup of 1024 per array:
 // thread t takes a run of consecutive counters, the runs' sums are scanned
 // across the workgroup, and each thread then writes the results of its run.
+// Runs of at most kScanRun counters are loaded at once and kept in
+// registers.
+constexpr uint32_t kScanRun = 8;
 __global__ void __launch_bounds__(1024) k_scan_degrees(const uint32_t* __restrict__ d0, uint32_t* __restrict__ o0,
                                                        const uint32_t* __restrict__ d1, uint32_t* __restrict__ o1,
                                                        uint32_t* __restrict__ c1, const uint32_t* __restrict__ d2,
@@ -509,18 +565,39 @@ __global__ void __launch_bounds__(1024) k_scan_degrees(const uint32_t* __restric
   const uint32_t m = n * R;
   const uint32_t per = (m + 1023) / 1024;
   const uint32_t t0 = min(m, threadIdx.x * per), t1 = min(m, t0 + per);
+  const bool short_run = per <= kScanRun;
+  uint32_t x[kScanRun];
   uint32_t sum = 0;
-  for (uint32_t t = t0; t < t1; ++t) sum += d[t];
+  if (short_run) {
+#pragma unroll
+    for (uint32_t j = 0; j < kScanRun; ++j) x[j] = t0 + j < t1 ? d[t0 + j] : 0u;
+#pragma unroll
+    for (uint32_t j = 0; j < kScanRun; ++j) sum += x[j];
+  } else {
+    for (uint32_t t = t0; t < t1; ++t) sum += d[t];
+  }
   uint32_t tot;
   uint32_t pre = wave_exclusive_scan(sum, &tot);
   if (lane == 0) wsum[wv] = tot;
   __syncthreads();
   for (uint32_t q = 0; q < wv; ++q) pre += wsum[q];
-  for (uint32_t t = t0; t < t1; ++t) {
-    const uint32_t x = d[t];
-    if (c) c[t] = pre;
-    if ((t & (R - 1)) == 0) o[t / R] = pre;
-    pre += x;
+  if (short_run) {
+#pragma unroll
+    for (uint32_t j = 0; j < kScanRun; ++j) {
+      const uint32_t t = t0 + j;
+      if (t < t1) {
+        if (c) c[t] = pre;
+        if ((t & (R - 1)) == 0) o[t / R] = pre;
+        pre += x[j];
+      }
+    }
+  } else {
+    for (uint32_t t = t0; t < t1; ++t) {
+      const uint32_t v = d[t];
+      if (c) c[t] = pre;
+      if ((t & (R - 1)) == 0) o[t / R] = pre;
+      pre += v;
+    }
   }
   if (threadIdx.x == 1023) o[n] = pre;
 }
