@@ -181,8 +181,9 @@ __global__ void k_dedup_insert(const uint32_t* __restrict__ sm, const uint64_t* 
                                unsigned long long* __restrict__ slot_of) {
   for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n_edges;
        i += uint64_t(gridDim.x) * blockDim.x) {
-    if (size[i] < 2) continue;
-    const unsigned long long h = hash[i];
+    const uint32_t si = size[i];
+    const unsigned long long h = hash[i];   // (loaded with the size)
+    if (si < 2) continue;
     const unsigned long long tag = h >> 32;
     const unsigned long long mine = (tag << 32) | i;
     unsigned long long pos = h & mask;
@@ -233,11 +234,13 @@ __global__ void __launch_bounds__(kTile) k_first_tiles(const uint32_t* __restric
   const uint64_t i = uint64_t(blockIdx.x) * kTile + threadIdx.x;
   uint32_t first = 0, s = 0, singles = 0, dups = 0, err = 0, err_at = 0xFFFFFFFFu;
   if (i < n_edges) {
+    // (slot_of[i] is loaded with the others; it is meaningful when s >= 2)
     s = size[i];
     err = ecode[i];
+    const unsigned long long so = slot_of[i];
     if (err) err_at = uint32_t(i);
     if (s >= 2) {
-      first = uint32_t(slots[slot_of[i]]) == uint32_t(i);
+      first = uint32_t(slots[so]) == uint32_t(i);
       dups = !first;
     } else if (s == 1) {
       singles = 1;
@@ -480,9 +483,11 @@ __global__ void __launch_bounds__(kTile) k_gather_tiles(const uint32_t* __restri
   if (bad) return;
   const uint64_t i = uint64_t(blockIdx.x) * kTile + threadIdx.x;
   uint32_t first = 0, s = 0;
+  uint64_t at = 0;   // the hyperedge's members in sm (loaded with its flags)
   if (i < n_edges) {
     first = first_in[i];
     s = size[i];
+    at = off[i];
   }
   uint32_t t[kTileN];
   tile_terms(first, s, t);
@@ -500,7 +505,7 @@ __global__ void __launch_bounds__(kTile) k_gather_tiles(const uint32_t* __restri
     for (int q = 0; q < wv; ++q) p += part[k][q];
     pos[k] = p;
   }
-  const uint32_t* m = sm + off[i];
+  const uint32_t* m = sm + at;
   // the first four members, loaded at once (the rest of a larger hyperedge
   // one by one)
   uint32_t mm[4];
@@ -650,22 +655,30 @@ __device__ void inc_fill(const uint32_t* __restrict__ e3, uint64_t n3, uint32_t*
                          uint32_t* __restrict__ oth3, unsigned long long* __restrict__ oth4, uint32_t block,
                          uint32_t n_blocks) {
   for (uint64_t i = uint64_t(block) * blockDim.x + threadIdx.x; i < n3 + n4; i += uint64_t(n_blocks) * blockDim.x) {
+    // (the cursors of all members are taken before any entry is written, so
+    // that the atomics go out together)
     if (i < n3) {
       const uint32_t cp = uint32_t(i) & (R - 1);
       const uint32_t m[3] = {e3[3 * i], e3[3 * i + 1], e3[3 * i + 2]};
+      uint32_t at[3];
+#pragma unroll
+      for (int j = 0; j < 3; ++j) at[j] = atomicAdd(&cur3[uint64_t(m[j]) * R + cp], 1u);
+#pragma unroll
       for (int j = 0; j < 3; ++j) {
-        const uint32_t at = atomicAdd(&cur3[uint64_t(m[j]) * R + cp], 1u);
-        idx3[at] = uint32_t(i);
-        if (oth3) oth3[at] = others3(m, j);
+        idx3[at[j]] = uint32_t(i);
+        if (oth3) oth3[at[j]] = others3(m, j);
       }
     } else {
       const uint64_t q = i - n3;
       const uint32_t cp = uint32_t(q) & (R - 1);
       const uint32_t m[4] = {e4[4 * q], e4[4 * q + 1], e4[4 * q + 2], e4[4 * q + 3]};
+      uint32_t at[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) at[j] = atomicAdd(&cur4[uint64_t(m[j]) * R + cp], 1u);
+#pragma unroll
       for (int j = 0; j < 4; ++j) {
-        const uint32_t at = atomicAdd(&cur4[uint64_t(m[j]) * R + cp], 1u);
-        idx4[at] = uint32_t(q);
-        if (oth4) oth4[at] = others4(m, j);
+        idx4[at[j]] = uint32_t(q);
+        if (oth4) oth4[at[j]] = others4(m, j);
       }
     }
   }
