@@ -643,12 +643,6 @@ int bits_for(uint64_t n) {
 // from H (a copy cannot hold more hyperedges of a size than H), so nothing
 // depends on host-side counts.
 
-__device__ inline unsigned long long tuple_hash_b(const uint32_t* m, uint32_t s) {
-  unsigned long long h = mix64(0x51ed270b27a3ffb1ull ^ s);
-  for (uint32_t i = 0; i < s; ++i) h = mix64(h ^ (m[i] + 0x9e3779b97f4a7c15ull * (i + 1)));
-  return h;
-}
-
 __global__ void k_b_prepare(uint32_t R, uint32_t E, uint64_t T, const unsigned long long* __restrict__ off,
                             uint32_t* __restrict__ members, unsigned long long* __restrict__ hash) {
   const uint64_t n = uint64_t(R) * E;
@@ -660,18 +654,26 @@ __global__ void k_b_prepare(uint32_t R, uint32_t E, uint64_t T, const unsigned l
       continue;
     }
     uint32_t* m = members + c * T + off[i];
+    // the members loaded at once and sorted by a network (padding, above any
+    // node id, sorts last)
     uint32_t r[4];
-    for (uint32_t j = 0; j < s; ++j) {
-      const uint32_t v = m[j];
-      uint32_t k = j;
-      while (k > 0 && r[k - 1] > v) {
-        r[k] = r[k - 1];
-        --k;
-      }
-      r[k] = v;
+#pragma unroll
+    for (uint32_t j = 0; j < 4; ++j) r[j] = j < s ? m[j] : 0xFFFFFFFFu;
+    constexpr int kNet[5][2] = {{0, 1}, {2, 3}, {0, 2}, {1, 3}, {1, 2}};
+#pragma unroll
+    for (int q = 0; q < 5; ++q) {
+      const uint32_t x = r[kNet[q][0]], y = r[kNet[q][1]];
+      r[kNet[q][0]] = min(x, y);
+      r[kNet[q][1]] = max(x, y);
     }
-    for (uint32_t j = 0; j < s; ++j) m[j] = r[j];
-    hash[idx] = tuple_hash_b(r, s);
+    unsigned long long h = mix64(0x51ed270b27a3ffb1ull ^ s);
+#pragma unroll
+    for (uint32_t j = 0; j < 4; ++j)
+      if (j < s) {
+        m[j] = r[j];
+        h = mix64(h ^ (r[j] + 0x9e3779b97f4a7c15ull * (j + 1)));
+      }
+    hash[idx] = h;
   }
 }
 
@@ -693,18 +695,16 @@ __global__ void k_b_dedup(uint32_t R, uint32_t E, uint64_t T, const unsigned lon
     const uint64_t c = idx / E;
     const uint32_t i = uint32_t(idx % E);
     const uint32_t s = uint32_t(off[i + 1] - off[i]);
+    const unsigned long long hi = hash[idx];   // (loaded with the size)
     if (s < 2 || s > 4) continue;
     uint32_t* t = tab + c * capD;
     const uint32_t* mc = members + c * T;
-    unsigned long long pos = hash[idx] & (capD - 1);
+    unsigned long long pos = hi & (capD - 1);
     while (true) {
-      uint32_t cur = t[pos];
-      if (cur == kEmpty32) {
-        const uint32_t prev = atomicCAS(&t[pos], kEmpty32, i);
-        if (prev == kEmpty32) break;
-        cur = prev;
-      }
-      if (hash[c * E + cur] == hash[idx] && same_copy_tuple(mc, off, cur, i)) {
+      // claim the slot if empty (most are: the table is at most half full)
+      const uint32_t cur = atomicCAS(&t[pos], kEmpty32, i);
+      if (cur == kEmpty32) break;
+      if (hash[c * E + cur] == hi && same_copy_tuple(mc, off, cur, i)) {
         atomicMin(&t[pos], i);
         break;
       }
@@ -722,15 +722,20 @@ __global__ void k_b_first(uint32_t R, uint32_t E, uint64_t T, const unsigned lon
     const uint64_t c = idx / E;
     const uint32_t i = uint32_t(idx % E);
     const uint32_t s = uint32_t(off[i + 1] - off[i]);
+    const unsigned long long hi = hash[idx];   // (loaded with the size)
     bool first = false;
     if (s >= 2 && s <= 4) {
       const uint32_t* t = tab + c * capD;
       const uint32_t* mc = members + c * T;
-      unsigned long long pos = hash[idx] & (capD - 1);
+      unsigned long long pos = hi & (capD - 1);
       while (true) {
         const uint32_t cur = t[pos];
         if (cur == kEmpty32) break;
-        if (hash[c * E + cur] == hash[idx] && same_copy_tuple(mc, off, cur, i)) {
+        if (cur == i) {   // the slot of i's tuple, holding i itself
+          first = true;
+          break;
+        }
+        if (hash[c * E + cur] == hi && same_copy_tuple(mc, off, cur, i)) {
           first = cur == i;
           break;
         }
@@ -853,14 +858,20 @@ __global__ void k_b_inc_fill(uint64_t cap_items, const uint32_t* __restrict__ to
   const uint64_t n = *total;
   for (uint64_t q = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; q < n && q < cap_items;
        q += uint64_t(gridDim.x) * blockDim.x) {
-    uint32_t m[J];
+    uint32_t m[J], at[J];
+    const uint64_t row = uint64_t(copyj[q]) * N;
+#pragma unroll
     for (int j = 0; j < J; ++j) m[j] = e[J * q + j];
+    // every member's cursor taken before any entry is written, so that the
+    // atomics go out together
+#pragma unroll
+    for (int j = 0; j < J; ++j) at[j] = atomicAdd(&cursor[row + m[j]], 1u);
+#pragma unroll
     for (int j = 0; j < J; ++j) {
-      const uint32_t at = atomicAdd(&cursor[uint64_t(copyj[q]) * N + m[j]], 1u);
-      idx[at] = uint32_t(q);
+      idx[at[j]] = uint32_t(q);
       if (oth) {
-        if constexpr (J == 3) oth[at] = others3(m, j);
-        else oth[at] = others4(m, j);
+        if constexpr (J == 3) oth[at[j]] = others3(m, j);
+        else oth[at[j]] = others4(m, j);
       }
     }
   }
