@@ -326,6 +326,9 @@ def main() -> int:
     ap.add_argument("--learned-only", action="store_true",
                     help="only train the learned proposal on the communication workload's 5%% subsample and draw "
                          "8 learned estimates at 0.15%% (for a kernel trace of the learned path)")
+    ap.add_argument("--nulls-only", action="store_true",
+                    help="only the 64-copy stub-matching null batch of the face-to-face workload: the first call "
+                         "(tuning and capture) and 5 replays (for a kernel trace of the null pipeline)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first copy 256 MiB device to device (a kernel of known traffic for counter scaling)")
     args = ap.parse_args()
@@ -368,6 +371,21 @@ def main() -> int:
         return 0
     if args.lookup_only:
         print(json.dumps({"large_workloads": large_workloads(hm, W, torch, exact_only=True)}))
+        return 0
+    if args.nulls_only:
+        h = W.cfg1_facetoface_k4(0)
+        stream = torch.cuda.current_stream()
+        g = hm.hm_graph_create(h.members, h.offsets, h.n_nodes, stream=stream)
+        t0 = time.perf_counter()
+        hm.count_nulls(g, 4, 64, 1, stream=stream)
+        first_ms = (time.perf_counter() - t0) * 1e3
+        t0 = time.perf_counter()
+        for i in range(5):
+            hm.count_nulls(g, 4, 64, 2 + i, stream=stream)
+        print(json.dumps({"nulls_only": {"copies": 64, "first_call_ms": first_ms,
+                                         "ms_per_batch": (time.perf_counter() - t0) * 1e3 / 5,
+                                         "tile_sizes": hm.hm_null_tile_sizes(g)}}))
+        g.close()
         return 0
     h = W.cfg1_facetoface_k4(0)
     members = torch.from_numpy(h.members.astype(np.int32)).to(dev)

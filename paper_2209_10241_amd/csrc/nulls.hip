@@ -1625,7 +1625,7 @@ int autotune(const hm_graph* H, NullPlan& P, hipStream_t st) {
   // items per tile: per wavefront, or with k_null_count_lds per workgroup
   // (its kWavesPerBlock wavefronts share a tile)
   static const uint32_t cand_wave[] = {1, 2, 4, 8, 16};
-  static const uint32_t cand_block[] = {16, 32, 64, 128, 256};
+  static const uint32_t cand_block[] = {64, 128, 256, 512, 1024};
   const uint32_t* cand_b = null_lds(P) ? cand_block : cand_wave;
   const uint32_t* cand_c = cand_b;
   hipEvent_t e0, e1;
