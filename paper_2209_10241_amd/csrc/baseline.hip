@@ -174,12 +174,15 @@ __global__ void k_base_combine(unsigned long long* __restrict__ hist, int n_clas
                                unsigned long long* __restrict__ stats) {
   __shared__ unsigned long long part[256 / kWave];
   const int c = threadIdx.x;
+  // every copy is loaded before any is cleared (the loads go out together)
+  unsigned long long x[kHistCopies];
+#pragma unroll
+  for (uint32_t q = 0; q < kHistCopies; ++q) x[q] = hist[uint64_t(q) * kExactHistStride + kMain + c];
   unsigned long long m = 0;
-  for (uint32_t q = 0; q < kHistCopies; ++q) {
-    unsigned long long* h = hist + uint64_t(q) * kExactHistStride + kMain;
-    m += h[c];
-    h[c] = 0;
-  }
+#pragma unroll
+  for (uint32_t q = 0; q < kHistCopies; ++q) m += x[q];
+#pragma unroll
+  for (uint32_t q = 0; q < kHistCopies; ++q) hist[uint64_t(q) * kExactHistStride + kMain + c] = 0;
   if (c < n_classes) counts[c] = int64_t(m);
   const unsigned long long s = wave_sum(m);
   if ((c & (kWave - 1)) == 0) part[c / kWave] = s;

@@ -64,20 +64,33 @@ struct ClassMask {
 
 // (one workgroup of 256 threads; sums the kHistCopies copies of hist and
 // leaves them zero)
-__global__ void k_combine(unsigned long long* __restrict__ hist, int n_classes, ClassMask pairs_only,
+__global__ void __launch_bounds__(256) k_combine(unsigned long long* __restrict__ hist, int n_classes, ClassMask pairs_only,
                           int64_t* __restrict__ counts, IdShapes sh) {
   __shared__ unsigned long long ids[8];
   const int c = threadIdx.x;
   // every copy is read before any is cleared, so that the loads go out
   // together rather than each behind the previous store
-  unsigned long long m = 0, s = 0, g = 0, a = 0;
+  // (all 4 x kHistCopies loads are issued before any is summed; the
+  // identity sums are read by every thread, inside the copy's stride, and
+  // kept by the first seven, since a conditional load would wait for the
+  // loads before it)
+  const bool ids_on = sh.on && c < 7;
+  unsigned long long lm[kHistCopies], ls[kHistCopies], lg[kHistCopies], la[kHistCopies];
 #pragma unroll
   for (uint32_t q = 0; q < kHistCopies; ++q) {
     const unsigned long long* h = hist + uint64_t(q) * kExactHistStride;
-    m += h[kMain + c];
-    s += h[kSub + c];
-    g += h[kG2 + c];
-    if (sh.on && c < 7) a += h[kIdAcc + c];
+    lm[q] = h[kMain + c];
+    ls[q] = h[kSub + c];
+    lg[q] = h[kG2 + c];
+    la[q] = h[kIdAcc + c];
+  }
+  unsigned long long m = 0, s = 0, g = 0, a = 0;
+#pragma unroll
+  for (uint32_t q = 0; q < kHistCopies; ++q) {
+    m += lm[q];
+    s += ls[q];
+    g += lg[q];
+    a += ids_on ? la[q] : 0ull;
   }
   __syncthreads();
 #pragma unroll

@@ -1034,11 +1034,16 @@ struct SampledLds<4, false> {
 // makes the atomics of every workgroup of the sampler visible to it.
 __global__ void __launch_bounds__(kThreads) k_finish_sampled(SampledArgs a, ScaleArgs sc) {
   const int c = threadIdx.x;
+  // every copy is loaded before any is cleared, so that the loads go out
+  // together rather than each behind the previous store
+  unsigned long long x[kHistCopies];
+#pragma unroll
+  for (uint32_t q = 0; q < kHistCopies; ++q) x[q] = a.hist[uint64_t(q) * kSampleHistStride + c];
   unsigned long long r = 0;
-  for (uint32_t q = 0; q < kHistCopies; ++q) {
-    r += a.hist[uint64_t(q) * kSampleHistStride + c];
-    a.hist[uint64_t(q) * kSampleHistStride + c] = 0;
-  }
+#pragma unroll
+  for (uint32_t q = 0; q < kHistCopies; ++q) r += x[q];
+#pragma unroll
+  for (uint32_t q = 0; q < kHistCopies; ++q) a.hist[uint64_t(q) * kSampleHistStride + c] = 0;
   if (a.est && c < a.n_classes) {
     const int j = sc.maxcard[c];
     double e = 0.0;
