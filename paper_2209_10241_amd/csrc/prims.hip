@@ -35,10 +35,16 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_tile(const T* __restrict_
   __shared__ T tile[kScanTile];
   __shared__ T wave_sums[kScanThreads / kWave];
   const uint64_t base = uint64_t(blockIdx.x) * kScanTile;
-  for (int i = threadIdx.x; i < kScanTile; i += kScanThreads) {
-    uint64_t g = base + i;
-    tile[i] = g < n ? in[g] : T(0);
+  // (all of the thread's loads before its LDS stores, so that they go out
+  // together)
+  T v[kScanItems];
+#pragma unroll
+  for (int r = 0; r < kScanItems; ++r) {
+    const uint64_t g = base + uint64_t(r) * kScanThreads + threadIdx.x;
+    v[r] = g < n ? in[g] : T(0);
   }
+#pragma unroll
+  for (int r = 0; r < kScanItems; ++r) tile[r * kScanThreads + threadIdx.x] = v[r];
   __syncthreads();
   T local[kScanItems];
   T s = 0;
@@ -117,10 +123,17 @@ __global__ void __launch_bounds__(kSortThreads) k_sort_hist(const unsigned long 
   counts[threadIdx.x] = 0;
   __syncthreads();
   const uint64_t base = uint64_t(blockIdx.x) * kSortTile;
+  // every key of the thread loaded before any is counted (the loads go out
+  // together rather than each behind the previous count)
+  uint32_t d[kSortItems];
+#pragma unroll
   for (int r = 0; r < kSortItems; ++r) {
-    uint64_t i = base + uint64_t(r) * kSortThreads + threadIdx.x;
-    if (i < n) atomicAdd(&counts[uint32_t(keys[i] >> shift) & digit_mask], 1u);
+    const uint64_t i = base + uint64_t(r) * kSortThreads + threadIdx.x;
+    d[r] = i < n ? uint32_t(keys[i] >> shift) & digit_mask : 0xFFFFFFFFu;
   }
+#pragma unroll
+  for (int r = 0; r < kSortItems; ++r)
+    if (d[r] != 0xFFFFFFFFu) atomicAdd(&counts[d[r]], 1u);
   __syncthreads();
   hist[uint64_t(threadIdx.x) * nb + blockIdx.x] = counts[threadIdx.x];
 }
