@@ -811,15 +811,15 @@ __device__ void sample_j2_k4_bits(const View& v, const Draws& d, uint32_t part, 
     // the second term (below) instead of reading it again
     const bool one_round = u1 - u0 <= kThreads;
     uint32_t own_x = 0xFFFFFFFFu, own_y = 0xFFFFFFFFu;
+    // (each entry carries the hyperedge's other two members, ascending)
     for (uint32_t p = u0 + tid; p < u1; p += kThreads) {
-      const uint32_t* t = v.e3 + 3ull * v.i3_idx[p];
-      const uint32_t t0 = t[0], t1 = t[1], t2 = t[2];
-      if (t0 == w || t1 == w || t2 == w) {
-        const uint32_t c = t0 ^ t1 ^ t2 ^ u ^ w;
+      const uint32_t o = v.i3_oth[p], y = o & 0xFFFFu, z = o >> 16;
+      if (y == w || z == w) {
+        const uint32_t c = y ^ z ^ w;
         atomicOr(&L.XS[c >> 5], 1u << (c & 31));
       } else {
-        own_x = t0 == u ? t1 : t0;
-        own_y = t2 == u ? t1 : t2;
+        own_x = y;
+        own_y = z;
       }
     }
     __syncthreads();
@@ -896,30 +896,26 @@ __device__ void sample_j2_k4_bits(const View& v, const Draws& d, uint32_t part, 
       if (own_x != 0xFFFFFFFFu) remove(own_x, own_y);
     } else {
       for (uint32_t p = u0 + tid; p < u1; p += kThreads) {
-        const uint32_t* t = v.e3 + 3ull * v.i3_idx[p];
-        if (t[0] == w || t[1] == w || t[2] == w) continue;
-        remove(t[0] == u ? t[1] : t[0], t[2] == u ? t[1] : t[2]);
+        const uint32_t o = v.i3_oth[p], y = o & 0xFFFFu, z = o >> 16;
+        if (y == w || z == w) continue;
+        remove(y, z);
       }
     }
     const uint32_t w0 = v.i3_off[w], w1 = v.i3_off[w + 1];
     for (uint32_t p = w0 + tid; p < w1; p += kThreads) {
-      const uint32_t* t = v.e3 + 3ull * v.i3_idx[p];
-      if (t[0] == u || t[1] == u || t[2] == u) continue;
-      const uint32_t x = t[0] == w ? t[1] : t[0], y = t[2] == w ? t[1] : t[2];
+      const uint32_t o = v.i3_oth[p], x = o & 0xFFFFu, y = o >> 16;   // w's hyperedge {w, x, y}
+      if (x == u || y == u) continue;
       if (has3(v.hs3, u, x, y)) continue;   // taken at u
       remove(x, y);
     }
     const uint32_t f0 = v.i4_off[u], f1 = v.i4_off[u + 1];
     for (uint32_t p = f0 + tid; p < f1; p += kThreads) {
-      const uint32_t* f = v.e4 + 4ull * v.i4_idx[p];
-      const uint32_t f_0 = f[0], f_1 = f[1], f_2 = f[2], f_3 = f[3];
-      if (f_0 != w && f_1 != w && f_2 != w && f_3 != w) continue;
+      // u's hyperedge {u, a, b, c}, a < b < c
+      const unsigned long long o = v.i4_oth[p];
+      const uint32_t a = uint32_t(o) & 0xFFFFu, b = uint32_t(o >> 16) & 0xFFFFu, c = uint32_t(o >> 32) & 0xFFFFu;
+      if (a != w && b != w && c != w) continue;
       // the two members other than u and w, ascending
-      uint32_t x = 0xFFFFFFFFu, y = 0xFFFFFFFFu;
-      for (const uint32_t m : {f_0, f_1, f_2, f_3}) {
-        if (m == u || m == w) continue;
-        if (x == 0xFFFFFFFFu) x = m; else y = m;
-      }
+      const uint32_t x = a == w ? b : a, y = c == w ? b : c;
       if (has3(v.hs3, u, x, y) || has3(v.hs3, w, x, y)) continue;   // taken at u or w
       remove(x, y);
     }
