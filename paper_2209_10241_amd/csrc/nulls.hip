@@ -459,8 +459,11 @@ __global__ void k_null_deal(uint32_t R, uint32_t E, uint64_t T, const unsigned l
 }
 
 // One workgroup per copy: repair rounds until no hyperedge repeats a node.
-// pre: k_null_bad has listed round 1's hyperedges (R <= gridDim.x, so the
-// workgroup's copy is its own index).
+// pre: k_null_deal has listed round 1's hyperedges (R <= gridDim.x, so the
+// workgroup's copy is its own index).  A round whose chosen list fits the LDS
+// sort (2 n_bad <= kLdsBitonic) keeps the list, the pool offsets and, when
+// the pool fits too, the pool and its keys in LDS; larger rounds use the
+// scratch arrays in device memory (the sort works on either).
 __global__ void __launch_bounds__(kThreads) k_null_repair(uint32_t c0, uint32_t R, uint32_t E, uint64_t T,
                                                           const unsigned long long* __restrict__ off,
                                                           uint32_t* __restrict__ members,
@@ -470,18 +473,20 @@ __global__ void __launch_bounds__(kThreads) k_null_repair(uint32_t c0, uint32_t 
   __shared__ uint32_t lstart[kBadLists + 1];
   __shared__ unsigned long long lk[kLdsBitonic];
   __shared__ uint32_t la[kLdsBitonic], lv[kLdsBitonic];
+  __shared__ uint32_t lchosen[kLdsBitonic], lpoff[kLdsBitonic];
   const unsigned long long seed = *seed_p;
   for (uint32_t c = blockIdx.x; c < R; c += gridDim.x) {
     uint32_t* m = members + uint64_t(c) * T;
     uint32_t* bad = sc.bad + uint64_t(blockIdx.x) * sc.bad_stride;
-    uint32_t* chosen = sc.chosen + uint64_t(blockIdx.x) * sc.chosen_pad;
-    unsigned long long* key = sc.key + uint64_t(blockIdx.x) * sc.pool_pad;
-    uint32_t* aux = sc.aux + uint64_t(blockIdx.x) * sc.pool_pad;
-    uint32_t* val = sc.val + uint64_t(blockIdx.x) * sc.pool_pad;
-    uint32_t* poff = sc.off + uint64_t(blockIdx.x) * sc.chosen_pad;
+    uint32_t* g_chosen = sc.chosen + uint64_t(blockIdx.x) * sc.chosen_pad;
+    unsigned long long* g_key = sc.key + uint64_t(blockIdx.x) * sc.pool_pad;
+    uint32_t* g_aux = sc.aux + uint64_t(blockIdx.x) * sc.pool_pad;
+    uint32_t* g_val = sc.val + uint64_t(blockIdx.x) * sc.pool_pad;
+    uint32_t* g_poff = sc.off + uint64_t(blockIdx.x) * sc.chosen_pad;
     const unsigned long long k1 = (kDomainNull << 32) | (c0 + c);
     // round 1 looks at every hyperedge (pre: k_null_deal did, into lists
-    // that are joined here through chosen); later rounds only at the last pool
+    // that are joined here through the chosen scratch); later rounds only at
+    // the last pool
     uint32_t n_bad = 0;
     if (pre) {
       if (threadIdx.x == 0) {
@@ -496,9 +501,9 @@ __global__ void __launch_bounds__(kThreads) k_null_repair(uint32_t c0, uint32_t 
       n_bad = lstart[kBadLists];
       for (uint32_t k = threadIdx.x / kWave; k < kBadLists; k += kWavesPerBlock)
         for (uint32_t j = lstart[k] + (threadIdx.x & (kWave - 1)); j < lstart[k + 1]; j += kWave)
-          chosen[j] = bad[k * sc.bad_cap + (j - lstart[k])];
+          g_chosen[j] = bad[k * sc.bad_cap + (j - lstart[k])];
       __syncthreads();
-      for (uint32_t q = threadIdx.x; q < n_bad; q += kThreads) bad[q] = chosen[q];
+      for (uint32_t q = threadIdx.x; q < n_bad; q += kThreads) bad[q] = g_chosen[q];
       __syncthreads();
     } else {
       n_bad = block_compact(E, [&](uint32_t i) {
@@ -507,15 +512,21 @@ __global__ void __launch_bounds__(kThreads) k_null_repair(uint32_t c0, uint32_t 
     }
     int r = 1;
     for (; n_bad > 0 && r <= kMaxRepairRounds; ++r) {
+      uint32_t pad = 1;
+      while (pad < 2 * n_bad) pad <<= 1;
+      const bool small = pad <= kLdsBitonic;   // uniform over the workgroup
+      uint32_t* chosen = small ? lchosen : g_chosen;
+      uint32_t* poff = small ? lpoff : g_poff;
+      unsigned long long* key = small ? lk : g_key;
+      uint32_t* aux = small ? la : g_aux;
+      uint32_t* tmp = small ? lv : bad;   // (bad is not read again in the round once copied)
       // partners, then the ascending union of bad and partners
       for (uint32_t q = threadIdx.x; q < 2 * n_bad; q += kThreads)
         chosen[q] = q < n_bad ? bad[q]
                               : uint32_t(bounded64(philox4x64_10(q - n_bad, uint64_t(r), 1, 0, seed, k1).v[0], E));
-      uint32_t pad = 1;
-      while (pad < 2 * n_bad) pad <<= 1;
       for (uint32_t q = 2 * n_bad + threadIdx.x; q < pad; q += kThreads) chosen[q] = 0xFFFFFFFFu;
       __syncthreads();
-      // sort the 32-bit list with the pool arrays as scratch (key = value)
+      // sort the 32-bit list with the key and aux arrays (key = value)
       for (uint32_t q = threadIdx.x; q < pad; q += kThreads) {
         key[q] = chosen[q];
         aux[q] = 0;
@@ -528,9 +539,9 @@ __global__ void __launch_bounds__(kThreads) k_null_repair(uint32_t c0, uint32_t 
         return q == 0 || chosen[q] != chosen[q - 1];
       }, aux, wsum);
       // aux[0..n_ch) = positions of first copies; gather them (ascending, unique)
-      for (uint32_t q = threadIdx.x; q < n_ch; q += kThreads) bad[q] = chosen[aux[q]];
+      for (uint32_t q = threadIdx.x; q < n_ch; q += kThreads) tmp[q] = chosen[aux[q]];
       __syncthreads();
-      for (uint32_t q = threadIdx.x; q < n_ch; q += kThreads) chosen[q] = bad[q];
+      for (uint32_t q = threadIdx.x; q < n_ch; q += kThreads) chosen[q] = tmp[q];
       __syncthreads();
       // pool offsets and gather
       uint32_t pool = 0;
@@ -547,38 +558,42 @@ __global__ void __launch_bounds__(kThreads) k_null_repair(uint32_t c0, uint32_t 
         if (threadIdx.x == 0) atomicOr(failed, 2u);
         break;
       }
+      uint32_t ppad = 1;
+      while (ppad < pool) ppad <<= 1;
+      const bool pool_small = small && ppad <= kLdsBitonic;
+      unsigned long long* pkey = pool_small ? lk : g_key;
+      uint32_t* paux = pool_small ? la : g_aux;
+      uint32_t* pval = pool_small ? lv : g_val;
       for (uint32_t q = threadIdx.x; q < n_ch; q += kThreads) {
         const unsigned long long b = off[chosen[q]];
         const uint32_t s = uint32_t(off[chosen[q] + 1] - b);
-        for (uint32_t t = 0; t < s; ++t) val[poff[q] + t] = m[b + t];
+        for (uint32_t t = 0; t < s; ++t) pval[poff[q] + t] = m[b + t];
       }
-      uint32_t ppad = 1;
-      while (ppad < pool) ppad <<= 1;
       __syncthreads();
       for (uint32_t t = threadIdx.x; t < ppad; t += kThreads) {
         if (t < pool) {
-          key[t] = philox4x64_10(t, uint64_t(r), 0, 0, seed, k1).v[0];
-          aux[t] = t;
+          pkey[t] = philox4x64_10(t, uint64_t(r), 0, 0, seed, k1).v[0];
+          paux[t] = t;
         } else {
-          key[t] = ~0ull;
-          aux[t] = 0xFFFFFFFFu;
-          val[t] = 0;
+          pkey[t] = ~0ull;
+          paux[t] = 0xFFFFFFFFu;
+          pval[t] = 0;
         }
       }
       __syncthreads();
-      block_bitonic(key, aux, val, ppad, lk, la, lv);
+      block_bitonic(pkey, paux, pval, ppad, lk, la, lv);
       // deal back and find the hyperedges that still repeat a node
       for (uint32_t q = threadIdx.x; q < n_ch; q += kThreads) {
         const unsigned long long b = off[chosen[q]];
         const uint32_t s = uint32_t(off[chosen[q] + 1] - b);
-        for (uint32_t t = 0; t < s; ++t) m[b + t] = val[poff[q] + t];
+        for (uint32_t t = 0; t < s; ++t) m[b + t] = pval[poff[q] + t];
       }
       __syncthreads();
       n_bad = block_compact(n_ch, [&](uint32_t q) {
         const unsigned long long b = off[chosen[q]];
         return repeats_node(m + b, uint32_t(off[chosen[q] + 1] - b));
-      }, aux, wsum);
-      for (uint32_t q = threadIdx.x; q < n_bad; q += kThreads) bad[q] = chosen[aux[q]];
+      }, paux, wsum);
+      for (uint32_t q = threadIdx.x; q < n_bad; q += kThreads) bad[q] = chosen[paux[q]];
       __syncthreads();
     }
     if (n_bad > 0 && threadIdx.x == 0) atomicOr(failed, 1u);
