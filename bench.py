@@ -139,6 +139,23 @@ def measured_traffic() -> dict:
     return out
 
 
+VALU_FILE = os.path.join(ROOT, "profiles", "valu_issue_k_exact4_bits_facetoface_N400_E30000.md")
+
+
+def measured_valu_issue():
+    """Fraction of the chip's VALU issue rate k_exact4_bits used (SQ_INSTS_VALU over
+    its trace duration, from the committed counter profile), if still current."""
+    try:
+        lines = open(VALU_FILE).read().splitlines()
+    except OSError:
+        return None
+    digest = next((l.split("`")[1] for l in lines if l.startswith("source digest:")), None)
+    frac = next((l.split("`")[1] for l in lines if l.startswith("VALU issue fraction:")), None)
+    if digest != exact_source_digest() or frac is None:
+        return None
+    return float(frac)
+
+
 LOOKUP_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_lookup_k_sp_b4_heavy_tailed.md")
 LOOKUP_SOURCES = ("sparse.hip", "hm_sparse.h", "hm_device.h", "hm_internal.h", "prims.hip")
 
@@ -565,8 +582,11 @@ def main() -> int:
         # word) 7 popcounts and about 21 further operations (28)
         ops = (units["id_edge_word_tasks"] * 4 + units["id_k4_word_tasks"] * 4
                + units["id_c4_pair_word_tasks"] * 3 + units["b4_word_tasks"] * 28)
+        # beside the op model: the share of the VALU issue rate the launch used
+        # (hardware counters), which shows what the op model leaves out
         roof = {"bound": "alu", "achieved": ops / avg_s / 1e12, "peak": ALU_PEAK_TOPS, "unit": "Tops/s",
-                "frac": ops / avg_s / 1e12 / ALU_PEAK_TOPS, "traffic": traffic.get(dom)}
+                "frac": ops / avg_s / 1e12 / ALU_PEAK_TOPS, "traffic": traffic.get(dom),
+                "valu_issue_frac": measured_valu_issue()}
     else:
         raise RuntimeError(f"unexpected dominant kernel {dom}")
     roof["kernel"] = dom
