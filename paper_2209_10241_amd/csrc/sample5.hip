@@ -220,7 +220,7 @@ struct Lds5 {
   uint32_t ball[kBallCap];
   uint32_t n_ball;
   uint32_t overflow;
-  uint32_t lkeys[kLocalCap];      // canonical + 1
+  uint32_t lkeys[kLocalCap];      // (stratum << 26 | raw pattern) + 1 (add_local)
   unsigned long long lcount[kLocalCap];
 };
 
@@ -235,9 +235,15 @@ __device__ inline bool ball_insert(Lds5& L, uint32_t node) {
   return false;
 }
 
-__device__ inline void add_local(Lds5& L, const Sampled5Args& a, uint32_t canon) {
-  const uint32_t key = canon + 1u;
-  uint32_t h = uint32_t(mix64(canon)) & (kLocalCap - 1);
+// The workgroup's counts are kept by raw pattern p and the stratum j of the
+// sample (key (j << 26 | p) + 1, 0 empty): patterns repeat across a sample's
+// candidate sets, so each distinct one is put in canonical form once, when
+// the table is flushed, rather than once per set.  A set that finds no room
+// goes to the class table at once.
+constexpr uint32_t kPatBits5 = 26;
+__device__ inline void add_local(Lds5& L, const Sampled5Args& a, uint32_t j, uint32_t p) {
+  const uint32_t key = ((j << kPatBits5) | p) + 1u;
+  uint32_t h = uint32_t(mix64(key)) & (kLocalCap - 1);
   for (int probes = 0; probes < 16; ++probes) {
     const uint32_t cur = atomicCAS(&L.lkeys[h], 0u, key);
     if (cur == 0u || cur == key) {
@@ -246,7 +252,7 @@ __device__ inline void add_local(Lds5& L, const Sampled5Args& a, uint32_t canon)
     }
     h = (h + 1) & (kLocalCap - 1);
   }
-  add_global(a, canon, 1ull);
+  add_global(a, canonical5(L.T, p), 1ull);
 }
 
 __global__ void __launch_bounds__(kThreads5) k_sampled5(Sampled5Args a, Tables5 tables) {
@@ -341,12 +347,13 @@ __global__ void __launch_bounds__(kThreads5) k_sampled5(Sampled5Args a, Tables5 
       }
       const uint32_t p = fill5(a, L.T, V);
       if (maxcard5(L.T, p) != j || !connected5(L.T, p)) continue;
-      add_local(L, a, canonical5(L.T, p));
+      add_local(L, a, uint32_t(j), p);
     }
   }
   __syncthreads();
   for (uint32_t x = threadIdx.x; x < kLocalCap; x += blockDim.x)
-    if (L.lkeys[x]) add_global(a, L.lkeys[x] - 1u, L.lcount[x]);
+    if (L.lkeys[x])
+      add_global(a, canonical5(L.T, (L.lkeys[x] - 1u) & ((1u << kPatBits5) - 1u)), L.lcount[x]);
 }
 
 // compact the device class table: flags then positions
