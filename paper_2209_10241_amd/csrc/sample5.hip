@@ -255,78 +255,155 @@ __device__ inline void add_local(Lds5& L, const Sampled5Args& a, uint32_t j, uin
   add_global(a, canonical5(L.T, p), 1ull);
 }
 
-__global__ void __launch_bounds__(kThreads5) k_sampled5(Sampled5Args a, Tables5 tables) {
+// Sample s of the launch: its stratum j and the position i of its hyperedge
+// in that stratum (explicit, or drawn from the seed).
+__device__ inline void sample_of(const Sampled5Args& a, uint64_t s, int* j_out, uint64_t* i_out) {
+  int j = 2;
+  uint64_t r = s;
+  while (r >= a.S[j]) r -= a.S[j++];
+  *j_out = j;
+  *i_out = a.idx[j] ? a.idx[j][r]
+                    : bounded64(philox4x64_10(r, 0, 0, 0, a.seed, (kDomainSample << 32) | uint64_t(j)).v[0], a.n[j]);
+}
+
+// The ball of a sampled hyperedge e (j nodes): every node within 5 - j hops
+// of e through hyperedges of size 2..4 (and, for j = 5, none), e's own
+// nodes left out, in L.ball[0 .. L.n_ball) in ascending node order, so that
+// every workgroup that builds it enumerates the same candidate sets in the
+// same order.  Returns false (L.overflow set) when it holds more than
+// kBallCap nodes.  Every thread of the workgroup calls this.
+__device__ bool ball5(Lds5& L, const Sampled5Args& a, const uint32_t* e, int j) {
+  const int need = 5 - j;
+  __syncthreads();   // the previous ball is no longer read
+  for (uint32_t x = threadIdx.x; x < 2 * kBallCap; x += blockDim.x) L.set[x] = 0u;
+  if (threadIdx.x == 0) {
+    L.n_ball = 0;
+    L.overflow = 0;
+  }
+  __syncthreads();
+  if (threadIdx.x < uint32_t(j)) ball_insert(L, e[threadIdx.x]);
+  __syncthreads();
+  // breadth-first: hop h takes the nodes added by hop h - 1 (e itself first)
+  uint32_t f0 = 0, f1 = 0;
+  for (int h = 0; h < need; ++h) {
+    const uint32_t nf = h == 0 ? uint32_t(j) : f1 - f0;
+    const int wv = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
+    for (uint32_t q = wv; q < nf; q += kThreads5 / kWave) {
+      const uint32_t u = h == 0 ? e[q] : L.ball[f0 + q];
+      // pairs
+      for (uint32_t t = a.v.g2_off[u] + lane; t < a.v.g2_off[u + 1]; t += kWave) {
+        const uint32_t w = a.v.g2_adj[t];
+        if (ball_insert(L, w)) {
+          const uint32_t at = atomicAdd(&L.n_ball, 1u);
+          if (at < kBallCap) L.ball[at] = w; else L.overflow = 1u;
+        }
+      }
+      for (int fs = 3; fs <= j && fs <= 4; ++fs) {
+        const uint32_t* off = fs == 3 ? a.v.i3_off : a.v.i4_off;
+        const uint32_t* idx = fs == 3 ? a.v.i3_idx : a.v.i4_idx;
+        const uint32_t* rows = fs == 3 ? a.v.e3 : a.v.e4;
+        for (uint32_t t = off[u] + lane; t < off[u + 1]; t += kWave) {
+          const uint32_t* f = rows + uint64_t(fs) * idx[t];
+          for (int m = 0; m < fs; ++m)
+            if (ball_insert(L, f[m])) {
+              const uint32_t at = atomicAdd(&L.n_ball, 1u);
+              if (at < kBallCap) L.ball[at] = f[m]; else L.overflow = 1u;
+            }
+        }
+      }
+    }
+    __syncthreads();
+    f0 = h == 0 ? 0u : f1;
+    f1 = min(L.n_ball, kBallCap);
+    if (L.overflow) break;
+  }
+  if (L.overflow) return false;
+  // ascending order (bitonic sort in LDS, padded with ~0 to a power of two)
+  const uint32_t nb = L.n_ball;
+  uint32_t pad = 1;
+  while (pad < nb) pad <<= 1;
+  for (uint32_t x = nb + threadIdx.x; x < pad; x += blockDim.x) L.ball[x] = 0xFFFFFFFFu;
+  __syncthreads();
+  for (uint32_t k = 2; k <= pad; k <<= 1)
+    for (uint32_t d = k >> 1; d > 0; d >>= 1) {
+      for (uint32_t x = threadIdx.x; x < pad; x += blockDim.x) {
+        const uint32_t y = x ^ d;
+        if (y <= x) continue;
+        const uint32_t vx = L.ball[x], vy = L.ball[y];
+        if ((vx > vy) == ((x & k) == 0)) {
+          L.ball[x] = vy;
+          L.ball[y] = vx;
+        }
+      }
+      __syncthreads();
+    }
+  return true;
+}
+
+// Candidate sets of a sample: the choices of 5 - j ball nodes (one set, e
+// itself, when j = 5).
+__device__ inline uint64_t candidates5(uint32_t nb, int j) {
+  const int need = 5 - j;
+  return need ? (nb >= uint64_t(need) ? binom(nb, need) : 0) : 1;
+}
+
+// Pass 1: every sample's number of candidate chunks (kChunk5 candidate sets
+// each; 0 when its ball or its candidates are too many, with the error bit
+// set).  One workgroup per sample.
+constexpr uint64_t kChunk5 = 1ull << 16;
+__global__ void __launch_bounds__(kThreads5) k_chunks5(Sampled5Args a, uint64_t total, uint32_t* __restrict__ chunks) {
+  __shared__ Lds5 L;
+  for (uint64_t s = blockIdx.x; s < total; s += gridDim.x) {
+    int j;
+    uint64_t i;
+    sample_of(a, s, &j, &i);
+    const uint32_t* e = edge_row(a, j, i);
+    uint32_t c = 0;
+    if (!ball5(L, a, e, j)) {
+      if (threadIdx.x == 0) atomicOr(a.err, kErrBall);
+    } else {
+      const uint64_t cand = candidates5(L.n_ball, j);
+      if (cand >= kMaxCandidates) {
+        if (threadIdx.x == 0) atomicOr(a.err, kErrWork);
+      } else {
+        c = uint32_t((cand + kChunk5 - 1) / kChunk5);
+      }
+    }
+    if (threadIdx.x == 0) chunks[s] = c;
+  }
+}
+
+// Pass 2: the tasks (sample, chunk), tasks [first[s], first[s + 1]) being
+// sample s's chunks (first: exclusive scan of the chunk counts, first[total]
+// their sum).  A workgroup takes tasks in turn, rebuilds the task's ball and
+// classifies the task's candidate sets: with the ball in ascending order,
+// candidate t is the t-th choice of 5 - j ball nodes in colex order.
+__global__ void __launch_bounds__(kThreads5) k_sampled5(Sampled5Args a, Tables5 tables, uint64_t total,
+                                                        const uint32_t* __restrict__ first) {
   __shared__ Lds5 L;
   for (uint32_t i = threadIdx.x; i < kLocalCap; i += blockDim.x) {
     L.lkeys[i] = 0u;
     L.lcount[i] = 0ull;
   }
   if (threadIdx.x == 0) L.T = tables;
-  const uint64_t total = a.S[2] + a.S[3] + a.S[4] + a.S[5];
-  for (uint64_t s = blockIdx.x; s < total; s += gridDim.x) {
-    // the sample's stratum j and draw index
-    int j = 2;
-    uint64_t r = s;
-    while (r >= a.S[j]) r -= a.S[j++];
-    const uint64_t i = a.idx[j] ? a.idx[j][r]
-                                : bounded64(philox4x64_10(r, 0, 0, 0, a.seed, (kDomainSample << 32) | uint64_t(j)).v[0],
-                                            a.n[j]);
+  const uint32_t n_tasks = first[total];
+  for (uint32_t task = blockIdx.x; task < n_tasks; task += gridDim.x) {
+    // the sample whose task range holds `task`
+    uint64_t lo = 0, hi = total;   // first[lo] <= task < first[hi]
+    while (hi - lo > 1) {
+      const uint64_t mid = (lo + hi) >> 1;
+      if (first[mid] <= task) lo = mid; else hi = mid;
+    }
+    const uint64_t s = lo;
+    int j;
+    uint64_t i;
+    sample_of(a, s, &j, &i);
     const uint32_t* e = edge_row(a, j, i);
     const int need = 5 - j;
-    __syncthreads();   // the previous sample's ball is no longer read
-    for (uint32_t x = threadIdx.x; x < 2 * kBallCap; x += blockDim.x) L.set[x] = 0u;
-    if (threadIdx.x == 0) {
-      L.n_ball = 0;
-      L.overflow = 0;
-    }
-    __syncthreads();
-    if (threadIdx.x < uint32_t(j)) ball_insert(L, e[threadIdx.x]);
-    __syncthreads();
-    // breadth-first: hop h takes the nodes added by hop h - 1 (e itself first)
-    uint32_t f0 = 0, f1 = 0;
-    for (int h = 0; h < need; ++h) {
-      const uint32_t nf = h == 0 ? uint32_t(j) : f1 - f0;
-      const int wv = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
-      for (uint32_t q = wv; q < nf; q += kThreads5 / kWave) {
-        const uint32_t u = h == 0 ? e[q] : L.ball[f0 + q];
-        // pairs
-        for (uint32_t t = a.v.g2_off[u] + lane; t < a.v.g2_off[u + 1]; t += kWave) {
-          const uint32_t w = a.v.g2_adj[t];
-          if (ball_insert(L, w)) {
-            const uint32_t at = atomicAdd(&L.n_ball, 1u);
-            if (at < kBallCap) L.ball[at] = w; else L.overflow = 1u;
-          }
-        }
-        for (int fs = 3; fs <= j && fs <= 4; ++fs) {
-          const uint32_t* off = fs == 3 ? a.v.i3_off : a.v.i4_off;
-          const uint32_t* idx = fs == 3 ? a.v.i3_idx : a.v.i4_idx;
-          const uint32_t* rows = fs == 3 ? a.v.e3 : a.v.e4;
-          for (uint32_t t = off[u] + lane; t < off[u + 1]; t += kWave) {
-            const uint32_t* f = rows + uint64_t(fs) * idx[t];
-            for (int m = 0; m < fs; ++m)
-              if (ball_insert(L, f[m])) {
-                const uint32_t at = atomicAdd(&L.n_ball, 1u);
-                if (at < kBallCap) L.ball[at] = f[m]; else L.overflow = 1u;
-              }
-          }
-        }
-      }
-      __syncthreads();
-      f0 = h == 0 ? 0u : f1;
-      f1 = min(L.n_ball, kBallCap);
-      if (L.overflow) break;
-    }
-    if (L.overflow) {
-      if (threadIdx.x == 0) atomicOr(a.err, kErrBall);
-      continue;
-    }
-    const uint64_t nb = need ? L.n_ball : 0;
-    const uint64_t cand = need ? (nb >= uint64_t(need) ? binom(nb, need) : 0) : 1;
-    if (cand >= kMaxCandidates) {
-      if (threadIdx.x == 0) atomicOr(a.err, kErrWork);
-      continue;
-    }
-    for (uint64_t t = threadIdx.x; t < cand; t += blockDim.x) {
+    if (!ball5(L, a, e, j)) continue;   // (pass 1 gave it no task)
+    const uint64_t cand = candidates5(L.n_ball, j);
+    const uint64_t c0 = uint64_t(task - first[s]) * kChunk5, c1 = min(cand, c0 + kChunk5);
+    for (uint64_t t = c0 + threadIdx.x; t < c1; t += blockDim.x) {
       uint32_t V[5];
       for (int m = 0; m < j; ++m) V[m] = e[m];
       // the t-th choice of `need` ball nodes, colex order
@@ -516,8 +593,17 @@ int sampled5(hm_graph* H, const uint32_t* const idx[6], const uint64_t S[6], uin
   a.err = static_cast<uint32_t*>(err);
   const Tables5 T = make_tables5();
   if (total) {
+    // pass 1: candidate chunks per sample; pass 2: the (sample, chunk) tasks
+    void *chunks = nullptr, *first = nullptr;
+    HM_TRY(get(&chunks, total * 4));
+    HM_TRY(get(&first, (total + 1) * 4));
+    k_chunks5<<<unsigned(std::min<uint64_t>(total, 4096)), kThreads5, 0, st>>>(a, total,
+                                                                               static_cast<uint32_t*>(chunks));
+    HM_HIP(hipGetLastError());
+    HM_TRY(scan_exclusive_u32(static_cast<uint32_t*>(chunks), static_cast<uint32_t*>(first), total,
+                              static_cast<uint32_t*>(first) + total, st));
     ProfileScope ps("k_sampled5", st);
-    k_sampled5<<<unsigned(std::min<uint64_t>(total, 4096)), kThreads5, 0, st>>>(a, T);
+    k_sampled5<<<4096, kThreads5, 0, st>>>(a, T, total, static_cast<const uint32_t*>(first));
     HM_HIP(hipGetLastError());
   }
   uint32_t host_err = 0;
