@@ -139,20 +139,64 @@ __device__ inline void add_global(const Sampled5Args& a, uint32_t canon, unsigne
 }
 
 // fill-in of the 5-node set V (ascending): bit b for the b-th subset
+// The subsets of the five local positions with at least two members, in
+// ascending mask order (the order of Tables5::sub_mask and of the pattern's
+// bits), as constants so that fill5's loops unroll to fixed subsets.
+constexpr uint8_t kSubMask5[kSub5] = {3,  5,  6,  7,  9,  10, 11, 12, 13, 14, 15, 17, 18,
+                                      19, 20, 21, 22, 23, 24, 25, 26, 27, 28, 29, 30, 31};
+
+// The 26-bit pattern of the ascending 5-node set V: bit b set when subset b
+// of V is a hyperedge.  The home slots of the ten 3-node and five 4-node
+// subsets are loaded before any probe is resolved, so that their latencies
+// overlap; a probe that meets another key continues from there.
 __device__ inline uint32_t fill5(const Sampled5Args& a, const Tables5& T, const uint32_t* V) {
+  (void)T;
   uint32_t p = 0;
+  ulonglong2 home[kSub5];
+#pragma unroll
   for (int b = 0; b < kSub5; ++b) {
-    const uint32_t m = T.sub_mask[b];
+    const uint32_t m = kSubMask5[b];
+    const int n = __builtin_popcount(m);
     uint32_t x[5];
-    int n = 0;
+    int k = 0;
+#pragma unroll
     for (int i = 0; i < 5; ++i)
-      if ((m >> i) & 1u) x[n++] = V[i];
-    bool has;
-    if (n == 2) has = pair_bit(a.v.hs2, a.v.bits, a.v.W, x[0], x[1]) != 0;
-    else if (n == 3) has = set128_has(a.v.hs3, key3(x[0], x[1], x[2]));
-    else if (n == 4) has = set128_has(a.v.hs4, key4(x[0], x[1], x[2], x[3]));
-    else has = has5(a.e5, a.hs5, a.hs5_mask, x);
-    p |= uint32_t(has) << b;
+      if ((m >> i) & 1u) x[k++] = V[i];
+    if (n == 2) {
+      p |= pair_bit(a.v.hs2, a.v.bits, a.v.W, x[0], x[1]) << b;
+    } else if (n == 3 || n == 4) {
+      const Key128 key = n == 3 ? key3(x[0], x[1], x[2]) : key4(x[0], x[1], x[2], x[3]);
+      const Set128& set = n == 3 ? a.v.hs3 : a.v.hs4;
+      home[b] = *reinterpret_cast<const ulonglong2*>(set.slot + 2 * (hash128(key) & set.mask));
+    }
+  }
+#pragma unroll
+  for (int b = 0; b < kSub5; ++b) {
+    const uint32_t m = kSubMask5[b];
+    const int n = __builtin_popcount(m);
+    uint32_t x[5];
+    int k = 0;
+#pragma unroll
+    for (int i = 0; i < 5; ++i)
+      if ((m >> i) & 1u) x[k++] = V[i];
+    if (n == 3 || n == 4) {
+      const Key128 key = n == 3 ? key3(x[0], x[1], x[2]) : key4(x[0], x[1], x[2], x[3]);
+      const Set128& set = n == 3 ? a.v.hs3 : a.v.hs4;
+      bool has = false;
+      ulonglong2 v = home[b];
+      if (v.x == key.hi && v.y == key.lo) {
+        has = true;
+      } else if (v.x != kEmpty64) {
+        Probe128 pr;
+        pr.key = key;
+        pr.pos = ((hash128(key) & set.mask) + 1) & set.mask;
+        pr.v = *reinterpret_cast<const ulonglong2*>(set.slot + 2 * pr.pos);
+        has = probe128_end(set, pr);
+      }
+      p |= uint32_t(has) << b;
+    } else if (n == 5) {
+      p |= uint32_t(has5(a.e5, a.hs5, a.hs5_mask, x)) << b;
+    }
   }
   return p;
 }
