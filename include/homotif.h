@@ -34,6 +34,11 @@
  *     pointers after a call returns.  A graph handle owns its device memory
  *     until hm_graph_destroy.  Calls that use one graph handle must be
  *     serialised (one stream at a time): the handle holds reusable scratch.
+ *     Calls on different handles may run at once from several host threads,
+ *     each on its own stream; what the library shares between them (the
+ *     device memory cache, the pinned report words, tuning and occupancy
+ *     caches) is guarded by locks.  Exceptions are stated per entry point
+ *     (count_exact_noalloc, the profiling calls).
  *   - Errors: every entry point returns HM_OK (0) or a negative HM_E* code and
  *     never aborts; on error outputs are left unspecified and hm_last_error()
  *     returns a message (thread-local).

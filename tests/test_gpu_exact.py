@@ -413,3 +413,51 @@ def test_hub_option_bounds(hm):
     with pytest.raises(hm.HMError):
         hm.hm_set_option(hm.HM_OPT_HUB_MIN_DEGREE, 1 << 32)
     assert hm.hm_get_option(hm.HM_OPT_HUB_MIN_DEGREE) == 256
+
+
+def test_concurrent_threads_own_streams(hm):
+    """Graphs built and counted from several host threads at once, each on its
+    own stream, as the benchmark's throughput measurement runs them: every
+    count equals the stored oracle counts, and an invalid input on one thread
+    fails there alone with its own message."""
+    import threading
+    import torch
+    dev = torch.device("cuda:0")
+    h = W.cfg1_facetoface_k4(0)
+    want = _golden("facetoface_N400_E30000", 4)
+    members = torch.from_numpy(h.members.astype(np.int32)).to(dev)
+    offsets = torch.from_numpy(h.offsets.astype(np.int64)).to(dev)
+    bad = members.clone()
+    bad[5] = h.n_nodes   # a node id out of range
+    n_threads, per = 3, 12
+    results, errors = {}, []
+
+    def worker(t):
+        try:
+            torch.cuda.set_device(dev)
+            st = torch.cuda.Stream()
+            out = []
+            for i in range(per):
+                if t == 2 and i % 4 == 1:
+                    with pytest.raises(hm.HMError, match="node id"):
+                        hm.hm_graph_create(bad, offsets, h.n_nodes, stream=st)
+                    continue
+                with hm.hm_graph_create(members, offsets, h.n_nodes, stream=st) as g:
+                    c = hm.count_exact(g, 4, stream=st)
+                st.synchronize()
+                out.append(c.cpu().numpy())
+            results[t] = out
+        except BaseException as e:
+            errors.append(e)
+
+    th = [threading.Thread(target=worker, args=(t,)) for t in range(n_threads)]
+    for x in th:
+        x.start()
+    for x in th:
+        x.join()
+    assert not errors, errors[0]
+    assert sorted(results) == list(range(n_threads))
+    for t, out in results.items():
+        assert len(out) == (per - 3 if t == 2 else per)
+        for c in out:
+            assert np.array_equal(c, want), t
