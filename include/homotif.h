@@ -489,11 +489,25 @@ int count_sampled_weighted_indices(const hm_graph* H, int k, const uint32_t* idx
  *                            read a bit instead of probing the hash set.  0
  *                            keeps none.  Taken when a graph's rows are
  *                            built; results do not depend on it.
+ *   HM_OPT_DEDUP_TAG_BITS    the build finds repeated hyperedges in one
+ *                            launch: each enters a hash table whose entries
+ *                            carry this many bits of its hash as a tag
+ *                            (default and maximum 32), and an entry it meets
+ *                            with an equal tag is taken as its copy; the
+ *                            next launch compares the members of every such
+ *                            meeting, and if two different hyperedges met,
+ *                            the build starts again with the exact search
+ *                            (members compared at insertion, one launch
+ *                            more).  Fewer bits make such meetings frequent
+ *                            (0: every probe meets), to exercise that path;
+ *                            -1 always uses the exact search.  The graph
+ *                            does not depend on it.
  * HM_EINVAL for an unknown option or a value out of range. */
 #define HM_OPT_BITSET_MAX_NODES 1
 #define HM_OPT_SAMPLE_CHUNK_SCALE 2
 #define HM_OPT_ONE_PASS_MAX_EDGES 3
 #define HM_OPT_HUB_MIN_DEGREE 4
+#define HM_OPT_DEDUP_TAG_BITS 5
 int hm_set_option(int option, int64_t value);
 int hm_get_option(int option, int64_t* value);
 

@@ -27,6 +27,7 @@ HM_OPT_BITSET_MAX_NODES = 1
 HM_OPT_SAMPLE_CHUNK_SCALE = 2
 HM_OPT_ONE_PASS_MAX_EDGES = 3
 HM_OPT_HUB_MIN_DEGREE = 4
+HM_OPT_DEDUP_TAG_BITS = 5
 HM_ALLOC_PROPORTIONAL = 0
 HM_ALLOC_PAPER = 1
 HM_NULL_STUBS = 0

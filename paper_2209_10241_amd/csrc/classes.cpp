@@ -143,6 +143,8 @@ std::atomic<uint64_t> g_one_pass_max_edges{kOnePassMaxEdges};
 uint64_t one_pass_max_edges() { return g_one_pass_max_edges.load(); }
 std::atomic<uint32_t> g_hub_min_degree{kHubMinDegree};
 uint32_t hub_min_degree() { return g_hub_min_degree.load(); }
+std::atomic<int> g_dedup_tag_bits{32};
+int dedup_tag_bits() { return g_dedup_tag_bits.load(); }
 
 const ClassTables& class_tables() {
   static const ClassTables t = build();
@@ -182,6 +184,7 @@ namespace {
 struct BlockInfo {
   int device;
   size_t bytes;
+  bool filled = false;   // every byte 0xFF once its release has completed
 };
 // the blocks of one dfree_on call, free once its event has completed
 struct Pending {
@@ -191,6 +194,7 @@ struct Pending {
 };
 std::mutex g_pool_mu;
 std::map<std::pair<int, size_t>, std::vector<void*>> g_free;
+std::map<std::pair<int, size_t>, std::vector<void*>> g_free_filled;   // idle blocks of all-0xFF bytes
 std::unordered_map<void*, BlockInfo> g_live;
 std::vector<Pending> g_pending;
 std::map<int, std::vector<hipEvent_t>> g_events;   // idle events per device
@@ -209,7 +213,7 @@ void cache_block(void* p, const BlockInfo& info) {
     (void)hipFree(p);
     return;
   }
-  g_free[{info.device, info.bytes}].push_back(p);
+  (info.filled ? g_free_filled : g_free)[{info.device, info.bytes}].push_back(p);
   g_cached_bytes += info.bytes;
 }
 
@@ -230,10 +234,12 @@ void reap_pending() {
   (void)hipGetLastError();
 }
 
-// caller holds g_pool_mu: a cached block of (dev, cls), or null
-void* take_cached(int dev, size_t cls) {
-  auto it = g_free.find({dev, cls});
-  if (it == g_free.end() || it->second.empty()) return nullptr;
+// caller holds g_pool_mu: a cached block of (dev, cls) (of all-0xFF bytes
+// when filled), or null
+void* take_cached(int dev, size_t cls, bool filled = false) {
+  auto& free = filled ? g_free_filled : g_free;
+  auto it = free.find({dev, cls});
+  if (it == free.end() || it->second.empty()) return nullptr;
   void* p = it->second.back();
   it->second.pop_back();
   g_cached_bytes -= cls;
@@ -270,6 +276,36 @@ int dalloc(void** p, size_t bytes) {
   std::lock_guard<std::mutex> lock(g_pool_mu);
   g_live[*p] = BlockInfo{dev, cls};
   return HM_OK;
+}
+
+int dalloc_filled(void** p, size_t bytes, bool* filled) {
+  *p = nullptr;
+  *filled = false;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) {
+    set_error("hipGetDevice failed");
+    return HM_EDEVICE;
+  }
+  const size_t cls = size_class(bytes ? bytes : 1);
+  {
+    std::lock_guard<std::mutex> lock(g_pool_mu);
+    *p = take_cached(dev, cls, true);
+    if (!*p && !g_pending.empty()) {
+      reap_pending();
+      *p = take_cached(dev, cls, true);
+    }
+    if (*p) {
+      *filled = true;
+      return HM_OK;
+    }
+  }
+  return dalloc(p, bytes);
+}
+
+void mark_filled(void* p) {
+  std::lock_guard<std::mutex> lock(g_pool_mu);
+  auto it = g_live.find(p);
+  if (it != g_live.end()) it->second.filled = true;
 }
 
 void dfree(void* p) {
@@ -358,6 +394,14 @@ int hm_set_option(int option, int64_t value) {
     hm::g_hub_min_degree.store(uint32_t(value));
     return HM_OK;
   }
+  if (option == HM_OPT_DEDUP_TAG_BITS) {
+    if (value < -1 || value > 32) {
+      hm::set_error("HM_OPT_DEDUP_TAG_BITS must be in [-1, 32]");
+      return HM_EINVAL;
+    }
+    hm::g_dedup_tag_bits.store(int(value));
+    return HM_OK;
+  }
   hm::set_error("unknown option %d", option);
   return HM_EINVAL;
 }
@@ -381,6 +425,10 @@ int hm_get_option(int option, int64_t* value) {
   }
   if (option == HM_OPT_HUB_MIN_DEGREE) {
     *value = int64_t(hm::g_hub_min_degree.load());
+    return HM_OK;
+  }
+  if (option == HM_OPT_DEDUP_TAG_BITS) {
+    *value = hm::g_dedup_tag_bits.load();
     return HM_OK;
   }
   hm::set_error("unknown option %d", option);

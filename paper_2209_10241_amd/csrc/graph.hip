@@ -22,6 +22,9 @@ enum : uint32_t {
   kErrBadId = 2u,
   kErrRepeat = 4u,
   kErrOffsets = 8u,
+  // not an error of the input: two different hyperedges met in one entry of
+  // the one-launch duplicate search, which the build then repeats exactly
+  kErrCollide = 16u,
 };
 
 struct DevFlags {
@@ -77,16 +80,31 @@ __device__ void multi_fill(const FillRegions& r) {
 
 __global__ void k_multi_fill(FillRegions r) { multi_fill(r); }
 
+// The duplicate search of one launch: a table of (tag << 32) | index
+// entries, all-ones when empty.  A hyperedge probes from its hash; an entry
+// with its tag (the hash's high half under tag_mask) is taken to be its copy,
+// and the entry keeps the smaller index (first occurrence).  The members are
+// compared one launch later (k_first_tiles), where a meeting of two different
+// hyperedges is reported (kErrCollide).
+struct FastDedup {
+  unsigned long long* slots;   // null: the exact search (k_dedup_insert) runs instead
+  unsigned long long mask;
+  unsigned long long tag_mask;
+  unsigned long long* slot_of;
+};
+
 // One thread per input hyperedge: copy its members, sort them, check ids and
-// repeats, record its size and hash.  Offsets start at 0, never decrease and
-// stay within the n_members entries of members.
+// repeats, record its size and hash, and (dd.slots set) enter it in the
+// duplicate search.  Offsets start at 0, never decrease and stay within the
+// n_members entries of members.
 //
 // Each hyperedge's error code (kErr* bits, 0 when valid) goes to ecode; the
-// workgroups also carry out `fills` (the tables the later kernels start from).
+// workgroups also carry out `fills` (the tables the later kernels start from;
+// not the duplicate search's, which is filled before the launch).
 __global__ void k_prepare(const uint32_t* __restrict__ members, const uint64_t* __restrict__ offsets,
                           uint64_t n_edges, uint64_t n_members, uint32_t n_nodes, uint32_t* __restrict__ sm,
                           uint32_t* __restrict__ size, unsigned long long* __restrict__ hash,
-                          uint8_t* __restrict__ ecode, FillRegions fills) {
+                          uint8_t* __restrict__ ecode, FillRegions fills, FastDedup dd) {
   // (the hyperedges first: their chain of dependent loads starts at once, and
   // the fills' stores follow it)
   for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n_edges;
@@ -155,6 +173,21 @@ __global__ void k_prepare(const uint32_t* __restrict__ members, const uint64_t* 
       }
       size[i] = s;
       hash[i] = h;
+      if (dd.slots && s >= 2) {
+        const unsigned long long tag = (h >> 32) & dd.tag_mask;
+        const unsigned long long mine = (tag << 32) | i;
+        unsigned long long pos = h & dd.mask;
+        while (true) {
+          const unsigned long long cur = atomicCAS(&dd.slots[pos], kEmpty64, mine);
+          if (cur == kEmpty64) break;
+          if ((cur >> 32) == tag) {
+            atomicMin(&dd.slots[pos], mine);
+            break;
+          }
+          pos = (pos + 1) & dd.mask;
+        }
+        dd.slot_of[i] = pos;
+      }
     }
     ecode[i] = uint8_t(err);
   }
@@ -224,12 +257,18 @@ __device__ inline void tile_terms(uint32_t first, uint32_t s, uint32_t t[kTileN]
   t[4] = first ? s : 0;
 }
 
+// (verify: the table came from the one-launch search, so a hyperedge that
+// met an earlier one compares their members, and a meeting of two different
+// hyperedges sets kErrCollide)
 __global__ void __launch_bounds__(kTile) k_first_tiles(const uint32_t* __restrict__ size, uint64_t n_edges,
                                                         const unsigned long long* __restrict__ slots,
                                                         const unsigned long long* __restrict__ slot_of,
                                                         const uint8_t* __restrict__ ecode,
                                                         uint8_t* __restrict__ first_out,
-                                                        uint32_t* __restrict__ tile_cnt) {
+                                                        uint32_t* __restrict__ tile_cnt, bool verify,
+                                                        const uint32_t* __restrict__ sm,
+                                                        const uint64_t* __restrict__ off,
+                                                        const unsigned long long* __restrict__ hash) {
   __shared__ uint32_t part[kTileS][kTile / kWave];
   const uint64_t i = uint64_t(blockIdx.x) * kTile + threadIdx.x;
   uint32_t first = 0, s = 0, singles = 0, dups = 0, err = 0, err_at = 0xFFFFFFFFu;
@@ -240,8 +279,10 @@ __global__ void __launch_bounds__(kTile) k_first_tiles(const uint32_t* __restric
     const unsigned long long so = slot_of[i];
     if (err) err_at = uint32_t(i);
     if (s >= 2) {
-      first = uint32_t(slots[so]) == uint32_t(i);
+      const uint32_t holder = uint32_t(slots[so]);
+      first = holder == uint32_t(i);
       dups = !first;
+      if (verify && !first && !same_tuple(sm, off, size, hash, holder, i)) err |= kErrCollide;
     } else if (s == 1) {
       singles = 1;
     }
@@ -411,6 +452,10 @@ struct GatherOut {
   bool self_offsets;
   Report* report;
   unsigned long long* dev_totals;
+  // the one-launch duplicate search's table, returned to all-ones: each
+  // first occurrence clears its entry (null: nothing to clear)
+  unsigned long long* dedup_clear;
+  const unsigned long long* slot_of;
 };
 
 __global__ void __launch_bounds__(kTile) k_gather_tiles(const uint32_t* __restrict__ sm,
@@ -484,10 +529,12 @@ __global__ void __launch_bounds__(kTile) k_gather_tiles(const uint32_t* __restri
   const uint64_t i = uint64_t(blockIdx.x) * kTile + threadIdx.x;
   uint32_t first = 0, s = 0;
   uint64_t at = 0;   // the hyperedge's members in sm (loaded with its flags)
+  unsigned long long so = 0;
   if (i < n_edges) {
     first = first_in[i];
     s = size[i];
     at = off[i];
+    if (g.dedup_clear) so = g.slot_of[i];   // (meaningful when first)
   }
   uint32_t t[kTileN];
   tile_terms(first, s, t);
@@ -499,6 +546,7 @@ __global__ void __launch_bounds__(kTile) k_gather_tiles(const uint32_t* __restri
   }
   __syncthreads();
   if (!first) return;
+  if (g.dedup_clear) g.dedup_clear[so] = kEmpty64;
   unsigned long long pos[kTileN];
   for (int k = 0; k < kTileN; ++k) {
     unsigned long long p = base[k] + pre[k];
@@ -898,8 +946,12 @@ struct FillList {
 // graphs wait after the counting pass and size everything exactly.  Kernels
 // after validation read the counts from the device and do nothing when the
 // input is invalid.
+// build() returns this when two different hyperedges met in the one-launch
+// duplicate search; the caller builds again with exact_dedup.
+constexpr int kRetryExactDedup = 1;
+
 int build(hm_graph* H, const uint32_t* members_in, const uint64_t* offsets_in, uint64_t n_edges, uint64_t n_members,
-          int mem_kind, hipStream_t st) {
+          int mem_kind, hipStream_t st, bool exact_dedup) {
   Temps tmp(st);
   if (n_members > 0xFFFFFFFFull) {
     set_error("more than 2^32-1 incidences are not supported");
@@ -933,11 +985,29 @@ int build(hm_graph* H, const uint32_t* members_in, const uint64_t* offsets_in, u
   // dedup table: a lower load (1/8 instead of 1/2) shortens the longest probe
   // chain, which sets the dedup kernel's time; kept at 1/2 for large inputs
   const unsigned long long cap = pow2_capacity(E <= (1ull << 20) ? 4 * E : E);
+  // the duplicate search: one launch (inserted by k_prepare into a table that
+  // is all-ones before it starts, and left that way by the gather), or the
+  // exact search of k_dedup_insert
+  const int tag_bits = dedup_tag_bits();
+  const bool fast_dedup = E > 0 && !exact_dedup && tag_bits >= 0;
+  bool table_filled = false;
+  if (fast_dedup) {
+    void* q = nullptr;
+    HM_TRY(dalloc_filled(&q, cap * sizeof(unsigned long long), &table_filled));
+    tmp.ptrs.push_back(q);
+    slots = static_cast<unsigned long long*>(q);
+    if (!table_filled) {
+      FillList f0;
+      f0.add(slots, cap, kEmpty64, 1);
+      f0.launch(st);
+    }
+  } else {
+    tmp.stage(&slots, cap);
+  }
   tmp.stage(&dev_totals, kTileN + 1);
   tmp.stage(&sm, n_members);
   tmp.stage(&size, E);
   tmp.stage(&hash, E);
-  tmp.stage(&slots, cap);
   tmp.stage(&slot_of, E);
   tmp.stage(&first, E);
   tmp.stage(&ecode, E);
@@ -1013,16 +1083,25 @@ int build(hm_graph* H, const uint32_t* members_in, const uint64_t* offsets_in, u
   // (in one pass the table is carved by allocate(), so it is added after)
   FillList fl;
   if (one_pass) HM_TRY(allocate(E, E, E, E, n_members, fl));
-  fl.add(slots, cap, kEmpty64, 1);
+  if (!fast_dedup) fl.add(slots, cap, kEmpty64, 1);
   if (!E) fl.launch(st);
   if (E) {
     // validate and sort; collapse repeated hyperedges onto first occurrences
     unsigned long long most = E;
     for (uint32_t k = 0; k < fl.r.n; ++k) most = std::max(most, fl.r.count[k]);
+    FastDedup dd{};
+    if (fast_dedup) {
+      dd.slots = slots;
+      dd.mask = cap - 1;
+      dd.tag_mask = tag_bits >= 32 ? 0xFFFFFFFFull : (1ull << tag_bits) - 1;
+      dd.slot_of = slot_of;
+    }
     k_prepare<<<grid_for(most), 256, 0, st>>>(members, offsets, E, n_members, H->n_nodes, sm, size, hash, ecode,
-                                              fl.r);
-    k_dedup_insert<<<grid_for(E), 256, 0, st>>>(sm, offsets, size, hash, E, slots, cap - 1, slot_of);
-    k_first_tiles<<<unsigned(n_tiles), kTile, 0, st>>>(size, E, slots, slot_of, ecode, first, tile_cnt);
+                                              fl.r, dd);
+    if (!fast_dedup)
+      k_dedup_insert<<<grid_for(E), 256, 0, st>>>(sm, offsets, size, hash, E, slots, cap - 1, slot_of);
+    k_first_tiles<<<unsigned(n_tiles), kTile, 0, st>>>(size, E, slots, slot_of, ecode, first, tile_cnt, fast_dedup,
+                                                        sm, offsets, hash);
     // in one pass with few tiles the gather sums the tile counts itself
     if (!self_offsets) k_tile_scan<<<1, 1024, 0, st>>>(tile_cnt, n_tiles, rep_dev, dev_totals);
     rep.st = st;
@@ -1035,6 +1114,7 @@ int build(hm_graph* H, const uint32_t* members_in, const uint64_t* offsets_in, u
     HM_TRY(wait_ready(&rep.p->ready, st));
     rep.pending = false;
     const DevFlags got = rep.p->flags;
+    if (got.err == kErrCollide) return kRetryExactDedup;
     if (got.err) {
       const char* what = (got.err & kErrOffsets) ? "offsets[0] is not 0, or offsets decrease or exceed n_members"
                          : (got.err & kErrEmpty) ? "an empty hyperedge"
@@ -1084,6 +1164,8 @@ int build(hm_graph* H, const uint32_t* members_in, const uint64_t* offsets_in, u
     g.self_offsets = self_offsets;
     g.report = rep_dev;
     g.dev_totals = dev_totals;
+    g.dedup_clear = fast_dedup ? slots : nullptr;
+    g.slot_of = slot_of;
     k_gather_tiles<<<unsigned(n_tiles), kTile, 0, st>>>(sm, offsets, size, E, first, tile_cnt, g);
   }
   HM_HIP(hipGetLastError());
@@ -1134,7 +1216,10 @@ int build(hm_graph* H, const uint32_t* members_in, const uint64_t* offsets_in, u
     k_pair_adj<<<grid_for(m), 256, 0, st>>>(keys, m, (1ull << B) - 1, H->g2_adj);
     HM_HIP(hipGetLastError());
   }
-  if (one_pass) return read_report();
+  if (one_pass) HM_TRY(read_report());
+  // the gather leaves the duplicate search's table all-ones again (it ran:
+  // the input is valid and no two different hyperedges met)
+  if (fast_dedup) mark_filled(slots);
   // no wait: later calls on the stream are ordered after the build, and the
   // temporaries return to the cache only once it has run
   return HM_OK;
@@ -1209,7 +1294,19 @@ int hm_graph_create(const uint32_t* members, const uint64_t* offsets, uint64_t n
   }
   H->n_nodes = n_nodes;
   H->n_input = n_edges;
-  int rc = hm::build(H, members, offsets, n_edges, n_members, mem_kind, st);
+  int rc = hm::build(H, members, offsets, n_edges, n_members, mem_kind, st, false);
+  if (rc == hm::kRetryExactDedup) {
+    // two different hyperedges met in the one-launch duplicate search: the
+    // graph is built again with the exact search
+    (void)hipStreamSynchronize(st);
+    hm::release(H);
+    const int device = H->device;
+    *H = hm_graph();
+    H->device = device;
+    H->n_nodes = n_nodes;
+    H->n_input = n_edges;
+    rc = hm::build(H, members, offsets, n_edges, n_members, mem_kind, st, true);
+  }
   if (rc != HM_OK) {
     (void)hipStreamSynchronize(st);
     hm::release(H);

@@ -42,6 +42,9 @@ uint64_t one_pass_max_edges();
 constexpr uint32_t kHubMinDegree = 256;
 constexpr uint64_t kHubRowBytes = 32ull << 20;
 uint32_t hub_min_degree();
+// bits of a hyperedge's hash kept as its tag in the build's one-launch
+// duplicate search (HM_OPT_DEDUP_TAG_BITS; -1: the exact search only)
+int dedup_tag_bits();
 
 // ----------------------------------------------------------------- errors
 void set_error(const char* fmt, ...);
@@ -201,6 +204,14 @@ void dfree(void* p);
 // recorded on st for the batch)
 void dfree_on(void* p, hipStream_t st);
 void dfree_on(void* const* ps, size_t n, hipStream_t st);
+// A block for a table whose idle state is every byte 0xFF: a cached block
+// left that way by its last user when one is free (*filled true), else any
+// block (*filled false: the caller fills it).  mark_filled(p) before the
+// release of p promises that the work enqueued before the release leaves it
+// all 0xFF again; a block released without it goes back to the ordinary
+// cache.
+int dalloc_filled(void** p, size_t bytes, bool* filled);
+void mark_filled(void* p);
 
 // Order-k counts of the pairs-only shapes and of case (b) without bit rows
 // into H->hist (case (a) is counted by the caller).

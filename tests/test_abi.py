@@ -72,7 +72,8 @@ def test_options_host_logic():
     cases = [(hm.HM_OPT_BITSET_MAX_NODES, 8192, [-1, 8193]),
              (hm.HM_OPT_SAMPLE_CHUNK_SCALE, 1, [0, 1025]),
              (hm.HM_OPT_ONE_PASS_MAX_EDGES, 1 << 20, [-1, (1 << 20) + 1]),
-             (hm.HM_OPT_HUB_MIN_DEGREE, 256, [-1, 1 << 32])]
+             (hm.HM_OPT_HUB_MIN_DEGREE, 256, [-1, 1 << 32]),
+             (hm.HM_OPT_DEDUP_TAG_BITS, 32, [-2, 33])]
     for opt, default, bad in cases:
         assert hm.hm_get_option(opt) == default
         for b in bad:

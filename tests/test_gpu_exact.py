@@ -461,3 +461,47 @@ def test_concurrent_threads_own_streams(hm):
         assert len(out) == (per - 3 if t == 2 else per)
         for c in out:
             assert np.array_equal(c, want), t
+
+
+@pytest.mark.parametrize("bit_rows", [True, False], ids=["bits", "hash"])
+@pytest.mark.parametrize("tag_bits", [0, 1, -1, 32])
+def test_duplicate_search_paths(hm, tag_bits, bit_rows):
+    """The build's duplicate search.  With 0 tag bits every probe meets the
+    first entry on its way, with 1 about half the meetings are of different
+    hyperedges: the build finds them one launch later and repeats the search
+    exactly.  -1 takes the exact search from the start, 32 is the default.
+    Strata, singleton and duplicate counts and the order-4 counts equal the
+    oracle's either way."""
+    hm.hm_set_option(hm.HM_OPT_DEDUP_TAG_BITS, tag_bits)
+    hm.hm_set_option(hm.HM_OPT_BITSET_MAX_NODES, 8192 if bit_rows else 0)
+    try:
+        for seed in range(6):
+            h = W.random_small(500 + seed, 40, 100 + 60 * seed, {1: 0.05, 2: 0.45, 3: 0.3, 4: 0.15, 5: 0.05},
+                               allow_dups=True)
+            nh = core.normalise(h)
+            with hm.hm_graph_create(h.members, h.offsets, h.n_nodes) as g:
+                st = g.stats()
+                assert (st["n2"], st["n3"], st["n4"]) == (nh.count(2), nh.count(3), nh.count(4)), seed
+                assert st["singletons"] == nh.n_dropped_singletons and st["duplicates"] == nh.n_duplicates, seed
+                for j in (2, 3, 4):
+                    assert np.array_equal(g.export(j).astype(np.int64), nh.edges(j)), (seed, j)
+                assert np.array_equal(hm.count_exact(g, 4).cpu().numpy(), core.count_exact(h, 4)), seed
+    finally:
+        hm.hm_set_option(hm.HM_OPT_DEDUP_TAG_BITS, 32)
+        hm.hm_set_option(hm.HM_OPT_BITSET_MAX_NODES, 8192)
+
+
+def test_invalid_input_then_valid_same_size(hm):
+    """A build that fails validation leaves its duplicate-search table
+    unreturned to the all-ones state; the next build of the same size must
+    not take it for a clean one.  Alternating invalid and valid builds of one
+    size keeps giving the oracle's counts."""
+    h = W.random_small(77, 50, 400, {2: 0.5, 3: 0.3, 4: 0.2}, allow_dups=True)
+    want = core.count_exact(h, 4)
+    bad = h.members.copy()
+    bad[3] = h.n_nodes
+    for _ in range(4):
+        with pytest.raises(hm.HMError, match="node id"):
+            hm.hm_graph_create(bad, h.offsets, h.n_nodes)
+        with hm.hm_graph_create(h.members, h.offsets, h.n_nodes) as g:
+            assert np.array_equal(hm.count_exact(g, 4).cpu().numpy(), want)
