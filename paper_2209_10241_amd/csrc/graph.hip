@@ -257,9 +257,26 @@ __device__ inline void tile_terms(uint32_t first, uint32_t s, uint32_t t[kTileN]
   t[4] = first ? s : 0;
 }
 
-// (verify: the table came from the one-launch search, so a hyperedge that
-// met an earlier one compares their members, and a meeting of two different
-// hyperedges sets kErrCollide)
+// Node degrees of the pairwise graph and of the 3- and 4-node incidence
+// lists are counted in R copies per node (R a power of two, node-major), so
+// that no counter takes more than about 1/R of its node's incidences: a
+// hyperedge counts in, and later fills through, the copy this hash of its
+// sorted members picks.
+__device__ inline uint32_t degree_copy(const uint32_t* m, uint32_t s, uint32_t R) {
+  uint32_t h = 0x9E3779B9u * s;
+  for (uint32_t j = 0; j < s; ++j) h = (h ^ m[j]) * 0x85EBCA6Bu;
+  return (h >> 16) & (R - 1);
+}
+
+struct Degrees {
+  uint32_t *deg2, *deg3, *deg4;
+  uint32_t R;
+};
+
+// Each first occurrence of size 2, 3 or 4 also counts its members' degrees
+// (deg).  (verify: the table came from the one-launch search, so a hyperedge
+// that met an earlier one compares their members, and a meeting of two
+// different hyperedges sets kErrCollide)
 __global__ void __launch_bounds__(kTile) k_first_tiles(const uint32_t* __restrict__ size, uint64_t n_edges,
                                                         const unsigned long long* __restrict__ slots,
                                                         const unsigned long long* __restrict__ slot_of,
@@ -268,21 +285,37 @@ __global__ void __launch_bounds__(kTile) k_first_tiles(const uint32_t* __restric
                                                         uint32_t* __restrict__ tile_cnt, bool verify,
                                                         const uint32_t* __restrict__ sm,
                                                         const uint64_t* __restrict__ off,
-                                                        const unsigned long long* __restrict__ hash) {
+                                                        const unsigned long long* __restrict__ hash,
+                                                        Degrees deg) {
   __shared__ uint32_t part[kTileS][kTile / kWave];
   const uint64_t i = uint64_t(blockIdx.x) * kTile + threadIdx.x;
   uint32_t first = 0, s = 0, singles = 0, dups = 0, err = 0, err_at = 0xFFFFFFFFu;
   if (i < n_edges) {
-    // (slot_of[i] is loaded with the others; it is meaningful when s >= 2)
+    // (slot_of[i] and the member offset are loaded with the others; they are
+    // meaningful when s >= 2)
     s = size[i];
     err = ecode[i];
     const unsigned long long so = slot_of[i];
+    const uint64_t at = off[i];
     if (err) err_at = uint32_t(i);
     if (s >= 2) {
+      // the entry's holder and the members go out together
       const uint32_t holder = uint32_t(slots[so]);
+      uint32_t mm[4];
+#pragma unroll
+      for (uint32_t j = 0; j < 4; ++j) mm[j] = j < s && s <= 4 ? sm[at + j] : 0u;
       first = holder == uint32_t(i);
       dups = !first;
-      if (verify && !first && !same_tuple(sm, off, size, hash, holder, i)) err |= kErrCollide;
+      const bool collide = verify && !first && !same_tuple(sm, off, size, hash, holder, i);
+      // (only a hyperedge that passed validation: its ids are below n)
+      if (first && s <= 4 && !err) {
+        uint32_t* d = s == 2 ? deg.deg2 : s == 3 ? deg.deg3 : deg.deg4;
+        const uint32_t cp = degree_copy(mm, s, deg.R);
+#pragma unroll
+        for (uint32_t j = 0; j < 4; ++j)
+          if (j < s) atomicAdd(&d[uint64_t(mm[j]) * deg.R + cp], 1u);
+      }
+      if (collide) err |= kErrCollide;
     } else if (s == 1) {
       singles = 1;
     }
@@ -440,11 +473,13 @@ struct GatherOut {
   Set128 hs3, hs4;
   uint32_t* bits;
   uint32_t W;
-  // degree counters, R (a power of two) per node, node-major: a hyperedge at
-  // position p of its stratum counts in copy p & (R - 1) of each member, so
-  // that no counter takes more than about 1/R of its node's incidences
-  uint32_t *deg2, *deg3, *deg4;
-  uint32_t R;
+  // scan: three workgroups after the tiles' scan the degree arrays (counted
+  // by k_first_tiles) into the row offsets o2, o3, o4 (n + 1 each) and the
+  // fill cursors c3, c4 (n * R each)
+  bool scan;
+  Degrees deg;
+  uint32_t n;
+  uint32_t *o2, *o3, *o4, *c3, *c4;
   // self_offsets: tile_cnt holds the raw tile counters (no k_tile_scan ran);
   // each workgroup sums those of the tiles before it, and workgroup 0 also
   // writes the report and dev_totals.  Otherwise dev_totals holds what
@@ -457,6 +492,45 @@ struct GatherOut {
   unsigned long long* dedup_clear;
   const unsigned long long* slot_of;
 };
+
+// Exclusive scan of one degree array d (n nodes x R copies) by the calling
+// workgroup: row offsets o[v] = (scan at v * R) for v = 0..n and, when c is
+// not null, the fill cursor of every (node, copy).  Thread t takes a run of
+// at most RUN consecutive counters (n * R <= RUN * blockDim.x), loaded at
+// once; wsum is LDS of blockDim.x / kWave words.
+template <uint32_t RUN>
+__device__ void scan_degree_array(const uint32_t* __restrict__ d, uint32_t* __restrict__ o,
+                                  uint32_t* __restrict__ c, uint32_t n, uint32_t R, uint32_t* wsum) {
+  const uint32_t lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+  const uint32_t m = n * R;
+  const uint32_t per = (m + blockDim.x - 1) / blockDim.x;
+  const uint32_t t0 = min(m, threadIdx.x * per), t1 = min(m, t0 + per);
+  uint32_t x[RUN];
+  uint32_t sum = 0;
+#pragma unroll
+  for (uint32_t j = 0; j < RUN; ++j) x[j] = t0 + j < t1 ? d[t0 + j] : 0u;
+#pragma unroll
+  for (uint32_t j = 0; j < RUN; ++j) sum += x[j];
+  uint32_t tot;
+  uint32_t pre = wave_exclusive_scan(sum, &tot);
+  if (lane == 0) wsum[wv] = tot;
+  __syncthreads();
+  for (uint32_t q = 0; q < wv; ++q) pre += wsum[q];
+#pragma unroll
+  for (uint32_t j = 0; j < RUN; ++j) {
+    const uint32_t t = t0 + j;
+    if (t < t1) {
+      if (c) c[t] = pre;
+      if ((t & (R - 1)) == 0) o[t / R] = pre;
+      pre += x[j];
+    }
+  }
+  // (the last thread's sum includes every run: the total)
+  if (threadIdx.x == blockDim.x - 1) o[n] = pre;
+}
+// counters per thread of the gather's scan workgroups
+constexpr uint32_t kGatherScanRun = 32;
+constexpr uint64_t kGatherScanMax = uint64_t(kGatherScanRun) * kTile;   // n * R at most
 
 __global__ void __launch_bounds__(kTile) k_gather_tiles(const uint32_t* __restrict__ sm,
                                                          const uint64_t* __restrict__ off,
@@ -471,8 +545,16 @@ __global__ void __launch_bounds__(kTile) k_gather_tiles(const uint32_t* __restri
   const int wv = threadIdx.x / kWave;
   const uint32_t lane = threadIdx.x & (kWave - 1);
   __shared__ uint32_t bad;
+  const uint64_t n_tiles = (n_edges + kTile - 1) / kTile;
+  if (blockIdx.x >= n_tiles) {
+    // a degree scan (g.scan): array blockIdx.x - n_tiles
+    const uint32_t a = uint32_t(blockIdx.x - n_tiles);
+    scan_degree_array<kGatherScanRun>(a == 0 ? g.deg.deg2 : a == 1 ? g.deg.deg3 : g.deg.deg4,
+                                      a == 0 ? g.o2 : a == 1 ? g.o3 : g.o4, a == 0 ? nullptr : a == 1 ? g.c3 : g.c4,
+                                      g.n, g.deg.R, part[0]);
+    return;
+  }
   if (g.self_offsets) {
-    const uint64_t n_tiles = (n_edges + kTile - 1) / kTile;
     const DevFlags f = tile_flags(tile_off, threadIdx.x, n_tiles, kTile);
     uint32_t before[kTileN], all[kTileN];
 #pragma unroll
@@ -576,9 +658,6 @@ __global__ void __launch_bounds__(kTile) k_gather_tiles(const uint32_t* __restri
       atomicOr(&g.bits[uint64_t(a) * g.W + (b >> 5)], 1u << (b & 31));
       atomicOr(&g.bits[uint64_t(b) * g.W + (a >> 5)], 1u << (a & 31));
     }
-    const uint32_t cp = uint32_t(pos[1]) & (g.R - 1);
-    atomicAdd(&g.deg2[uint64_t(a) * g.R + cp], 1u);
-    atomicAdd(&g.deg2[uint64_t(b) * g.R + cp], 1u);
   } else if (s == 3 || s == 4) {
     uint32_t* e = s == 3 ? g.e3 + 3 * pos[2] : g.e4 + 4 * pos[3];
 #pragma unroll
@@ -589,11 +668,6 @@ __global__ void __launch_bounds__(kTile) k_gather_tiles(const uint32_t* __restri
     unsigned long long h = hash128(key) & set.mask;
     while (atomicCAS(set.slot + 2 * h, kEmpty64, key.hi) != kEmpty64) h = (h + 1) & set.mask;
     set.slot[2 * h + 1] = key.lo;
-    uint32_t* deg = s == 3 ? g.deg3 : g.deg4;
-    const uint32_t cp = uint32_t(s == 3 ? pos[2] : pos[3]) & (g.R - 1);
-#pragma unroll
-    for (uint32_t j = 0; j < 4; ++j)
-      if (j < s) atomicAdd(&deg[uint64_t(mm[j]) * g.R + cp], 1u);
   }
 }
 
@@ -694,7 +768,7 @@ __device__ void rows_from_bits(const uint32_t* __restrict__ bits, uint32_t n, ui
 }
 
 // Incidence lists of the 3- and 4-node hyperedges (positions in any order):
-// hyperedge i fills through the cursor of copy i & (R - 1) of each member,
+// a hyperedge fills through the cursor of copy degree_copy() of each member,
 // the copy its degree was counted in (workgroup `block` of `n_blocks`).
 // With bit rows (oth3, oth4 not null) each entry also gets the hyperedge's
 // other members.
@@ -706,8 +780,8 @@ __device__ void inc_fill(const uint32_t* __restrict__ e3, uint64_t n3, uint32_t*
     // (the cursors of all members are taken before any entry is written, so
     // that the atomics go out together)
     if (i < n3) {
-      const uint32_t cp = uint32_t(i) & (R - 1);
       const uint32_t m[3] = {e3[3 * i], e3[3 * i + 1], e3[3 * i + 2]};
+      const uint32_t cp = degree_copy(m, 3, R);
       uint32_t at[3];
 #pragma unroll
       for (int j = 0; j < 3; ++j) at[j] = atomicAdd(&cur3[uint64_t(m[j]) * R + cp], 1u);
@@ -718,8 +792,8 @@ __device__ void inc_fill(const uint32_t* __restrict__ e3, uint64_t n3, uint32_t*
       }
     } else {
       const uint64_t q = i - n3;
-      const uint32_t cp = uint32_t(q) & (R - 1);
       const uint32_t m[4] = {e4[4 * q], e4[4 * q + 1], e4[4 * q + 2], e4[4 * q + 3]};
+      const uint32_t cp = degree_copy(m, 4, R);
       uint32_t at[4];
 #pragma unroll
       for (int j = 0; j < 4; ++j) at[j] = atomicAdd(&cur4[uint64_t(m[j]) * R + cp], 1u);
@@ -977,6 +1051,9 @@ int build(hm_graph* H, const uint32_t* members_in, const uint64_t* offsets_in, u
   const bool self_offsets = one_pass && n_tiles <= kSelfOffsetTiles;
   const uint32_t R = degree_copies(N);
   const uint64_t NR = N * R;
+  // the degree scans ride on the gather's launch when its workgroups can
+  // hold a run each (else a launch of their own after it)
+  const bool gather_scan = E > 0 && NR <= kGatherScanMax;
 
   unsigned long long* dev_totals = nullptr;
   uint32_t *sm = nullptr, *size = nullptr, *tile_cnt = nullptr;
@@ -1004,6 +1081,12 @@ int build(hm_graph* H, const uint32_t* members_in, const uint64_t* offsets_in, u
   } else {
     tmp.stage(&slots, cap);
   }
+  // degree counters (counted by k_first_tiles, so staged and filled with the
+  // first temporaries in either kind of build)
+  uint32_t *deg2 = nullptr, *deg3 = nullptr, *deg4 = nullptr, *cur3 = nullptr, *cur4 = nullptr;
+  tmp.stage(&deg2, NR);
+  tmp.stage(&deg3, NR);
+  tmp.stage(&deg4, NR);
   tmp.stage(&dev_totals, kTileN + 1);
   tmp.stage(&sm, n_members);
   tmp.stage(&size, E);
@@ -1026,7 +1109,6 @@ int build(hm_graph* H, const uint32_t* members_in, const uint64_t* offsets_in, u
   }
 
   // buffers sized by the unique counts (bounds in one pass), and their fills
-  uint32_t *deg2 = nullptr, *deg3 = nullptr, *deg4 = nullptr, *cur3 = nullptr, *cur4 = nullptr;
   auto allocate = [&](uint64_t n2, uint64_t n3, uint64_t n4, uint64_t n_unique, uint64_t n_unique_members,
                       FillList& fl) -> int {
     Carve own;
@@ -1048,9 +1130,6 @@ int build(hm_graph* H, const uint32_t* members_in, const uint64_t* offsets_in, u
       own.add(&H->i3_oth, 3 * n3);
       own.add(&H->i4_oth, 4 * n4);
     }
-    tmp.stage(&deg2, NR);
-    tmp.stage(&deg3, NR);
-    tmp.stage(&deg4, NR);
     tmp.stage(&cur3, NR + 1);
     tmp.stage(&cur4, NR + 1);
     own.add(&H->g2_off, N + 1);
@@ -1072,9 +1151,6 @@ int build(hm_graph* H, const uint32_t* members_in, const uint64_t* offsets_in, u
     fl.add(H->hs4.slot, 2 * c4, kEmpty64, 1);
     fl.add(H->sample_hist, uint64_t(kHistCopies) * kSampleHistStride + 8, 0, 1);
     fl.add(H->hist, uint64_t(kHistCopies) * kExactHistStride, 0, 1);
-    fl.add(deg2, NR, 0, 0);
-    fl.add(deg3, NR, 0, 0);
-    fl.add(deg4, NR, 0, 0);
     if (keep_bits) fl.add(H->bits, N * H->words, 0, 0);
     fl.add(H->all_off, 1, 0, 1);   // all_off[0]; the rest is written by the gather
     return HM_OK;
@@ -1084,6 +1160,9 @@ int build(hm_graph* H, const uint32_t* members_in, const uint64_t* offsets_in, u
   FillList fl;
   if (one_pass) HM_TRY(allocate(E, E, E, E, n_members, fl));
   if (!fast_dedup) fl.add(slots, cap, kEmpty64, 1);
+  fl.add(deg2, NR, 0, 0);
+  fl.add(deg3, NR, 0, 0);
+  fl.add(deg4, NR, 0, 0);
   if (!E) fl.launch(st);
   if (E) {
     // validate and sort; collapse repeated hyperedges onto first occurrences
@@ -1101,7 +1180,7 @@ int build(hm_graph* H, const uint32_t* members_in, const uint64_t* offsets_in, u
     if (!fast_dedup)
       k_dedup_insert<<<grid_for(E), 256, 0, st>>>(sm, offsets, size, hash, E, slots, cap - 1, slot_of);
     k_first_tiles<<<unsigned(n_tiles), kTile, 0, st>>>(size, E, slots, slot_of, ecode, first, tile_cnt, fast_dedup,
-                                                        sm, offsets, hash);
+                                                        sm, offsets, hash, Degrees{deg2, deg3, deg4, R});
     // in one pass with few tiles the gather sums the tile counts itself
     if (!self_offsets) k_tile_scan<<<1, 1024, 0, st>>>(tile_cnt, n_tiles, rep_dev, dev_totals);
     rep.st = st;
@@ -1157,25 +1236,31 @@ int build(hm_graph* H, const uint32_t* members_in, const uint64_t* offsets_in, u
     g.hs4 = H->hs4;
     g.bits = H->bits;
     g.W = H->words;
-    g.deg2 = deg2;
-    g.deg3 = deg3;
-    g.deg4 = deg4;
-    g.R = R;
+    g.scan = gather_scan;
+    g.deg = Degrees{deg2, deg3, deg4, R};
+    g.n = uint32_t(N);
+    g.o2 = H->g2_off;
+    g.o3 = H->i3_off;
+    g.o4 = H->i4_off;
+    g.c3 = cur3;
+    g.c4 = cur4;
     g.self_offsets = self_offsets;
     g.report = rep_dev;
     g.dev_totals = dev_totals;
     g.dedup_clear = fast_dedup ? slots : nullptr;
     g.slot_of = slot_of;
-    k_gather_tiles<<<unsigned(n_tiles), kTile, 0, st>>>(sm, offsets, size, E, first, tile_cnt, g);
+    k_gather_tiles<<<unsigned(n_tiles) + (gather_scan ? 3u : 0u), kTile, 0, st>>>(sm, offsets, size, E, first,
+                                                                                  tile_cnt, g);
   }
   HM_HIP(hipGetLastError());
 
   // row offsets: pairwise rows, incidence lists of 3- and 4-node hyperedges;
-  // fill cursors per (node, copy)
-  if (NR <= 64 * 1024) {
+  // fill cursors per (node, copy) (with gather_scan, done by the gather's
+  // last three workgroups)
+  if (!gather_scan && NR <= 64 * 1024) {
     k_scan_degrees<<<3, 1024, 0, st>>>(deg2, H->g2_off, deg3, H->i3_off, cur3, deg4, H->i4_off, cur4, uint32_t(N), R);
     HM_HIP(hipGetLastError());
-  } else {
+  } else if (!gather_scan) {
     uint32_t* cur2 = nullptr;
     HM_TRY(tmp.get(&cur2, NR + 1));
     HM_TRY(scan_exclusive_u32(deg2, cur2, NR, cur2 + NR, st));
