@@ -16,7 +16,6 @@ import os
 import platform
 import sys
 import time
-from concurrent.futures import ThreadPoolExecutor
 
 import numpy as np
 
@@ -30,9 +29,10 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_exact_k4_facetoface_N
 EXACT_SOURCES = ("exact.hip", "hm_items.h", "hm_b4.h", "hm_device.h", "hm_internal.h")
 HBM_PEAK_GBS = 8000.0
 # integer VALU issue rate: 256 CUs x 64 lanes per cycle x 2.4 GHz
-# host threads (one stream each) that the headline measurement spreads its
-# hypergraphs over; three measured best (four gained nothing more)
-PIPELINE = 3
+# worker threads (one stream each) of the count_exact_many call that the
+# headline measurement makes: 3 gave 36 us per hypergraph, 7 or 8 about 31.5,
+# 10 to 16 no better
+PIPELINE = 8
 ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 
 
@@ -431,34 +431,23 @@ def main() -> int:
     sequential_ms = (time.perf_counter() - t0) * 1e3 / args.steps
     total = int(counts.sum().item())
 
-    # whole-job throughput: the K hypergraphs shared among PIPELINE host
-    # threads, each with its own stream.  A build ends with the host waiting
-    # for its validation report, so one thread leaves the GPU idle during that
-    # wait and while it issues the next launches; with several, one
+    # whole-job throughput: the K hypergraphs in one call of count_exact_many,
+    # whose PIPELINE worker threads build and count them on streams of their
+    # own.  A build ends with the host waiting for its validation report, so
+    # one hypergraph after another leaves the GPU idle during that wait and
+    # while the next launches are issued; with several workers one
     # hypergraph's build runs on the CUs beside another's count.
-    streams = [torch.cuda.Stream() for _ in range(PIPELINE)]
-    outs = [torch.zeros_like(counts) for _ in range(PIPELINE)]
-
-    def worker(t, m):
-        torch.cuda.set_device(dev)
-        for _ in range(m):
-            step(streams[t], outs[t])
-
-    # (the warmup starts the pool's threads, so the timed steps do not)
-    with ThreadPoolExecutor(PIPELINE) as pool:
-        def run_steps(n):
-            for f in [pool.submit(worker, t, n // PIPELINE + (t < n % PIPELINE)) for t in range(PIPELINE)]:
-                f.result()
-
-        run_steps(max(args.warmup, PIPELINE))
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        run_steps(args.steps)
-        torch.cuda.synchronize()
-        ms_per_step = (time.perf_counter() - t0) * 1e3 / args.steps
-    for o in outs:
-        if not torch.equal(o, counts):
-            raise RuntimeError("a pipelined count differs from the sequential one")
+    many_out = torch.empty((max(args.steps, args.warmup, PIPELINE), counts.numel()), dtype=torch.int64, device=dev)
+    hm.count_exact_many([(members, offsets, h.n_nodes)] * max(args.warmup, PIPELINE), 4, workers=PIPELINE,
+                        out=many_out, stream=stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    hm.count_exact_many([(members, offsets, h.n_nodes)] * args.steps, 4, workers=PIPELINE, out=many_out,
+                        stream=stream)
+    torch.cuda.synchronize()
+    ms_per_step = (time.perf_counter() - t0) * 1e3 / args.steps
+    if not bool((many_out[:args.steps] == counts.unsqueeze(0)).all()):
+        raise RuntimeError("a pipelined count differs from the sequential one")
 
     # counting alone on a resident graph, and per-kernel event timing
     g = hm.hm_graph_create(members, offsets, h.n_nodes, stream=stream)
@@ -701,8 +690,9 @@ def main() -> int:
         "config": {"workload": "facetoface_N400_E30000", "k": 4, "seed": 0, "n_nodes": h.n_nodes,
                    "unique_by_size": [stats["n2"], stats["n3"], stats["n4"], stats["n5plus"]],
                    "connected_4_sets": total},
-        "pipeline": {"threads": PIPELINE, "streams": PIPELINE,
-                     "what": "the K hypergraphs shared among host threads, one stream each"},
+        "pipeline": {"workers": PIPELINE, "streams": PIPELINE,
+                     "what": "the K hypergraphs in one count_exact_many call: worker threads of the library, "
+                             "one stream each"},
         "sequential_ms_per_hypergraph": sequential_ms,
         "count_only_ms": count_ms,
         "baseline_algorithm1": baseline,

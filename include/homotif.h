@@ -136,6 +136,28 @@ int hm_graph_export(const hm_graph* H, int j, uint32_t* out);
  * overwritten.  Asynchronous on `stream`. */
 int count_exact(const hm_graph* H, int k, int64_t* counts, void* stream);
 
+/* Exact counts of every order-k motif (k = 3 or 4, as count_exact) of each
+ * of n_graphs hypergraphs: hypergraph g is members[g], offsets[g],
+ * n_edges[g], n_members[g], n_nodes[g] with the meaning hm_graph_create
+ * gives them (members and offsets in the memory mem_kind names; the five
+ * arrays of n_graphs entries are host memory), and its counts go to
+ * counts[g * hm_num_classes(k) ...] (device, overwritten).  The hypergraphs
+ * are shared among `workers` host threads (1..16), each building, counting
+ * and releasing its graphs on a stream of its own (the library keeps these
+ * streams per device for the process), so that one graph's build, which
+ * waits for its validation on the host, runs beside another's count.  The
+ * workers start after the work already enqueued on `stream`, and `stream`
+ * waits for all of theirs: the counts are valid once it has synchronised.
+ * The call returns once every graph has been validated.
+ * Errors: HM_EINVAL for n_graphs < 0, workers outside 1..16, a NULL array,
+ * or a hypergraph that hm_graph_create refuses (any of its errors; the
+ * message names the lowest such graph index among those attempted, and the
+ * workers take no new graph after a failure, leaving the counts of graphs
+ * not reached unspecified); HM_EUNSUPPORTED for k other than 3 or 4. */
+int count_exact_many(int n_graphs, const uint32_t* const* members, const uint64_t* const* offsets,
+                     const uint64_t* n_edges, const uint64_t* n_members, const uint32_t* n_nodes, int mem_kind,
+                     int k, int64_t* counts, int workers, void* stream);
+
 /* count_exact for callers that cannot allocate device memory: code under
  * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
  * Same arguments, same counts, and no hipMalloc, hipFree or other device

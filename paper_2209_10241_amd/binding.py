@@ -67,6 +67,7 @@ SIGNATURES = {
     "hm_graph_stats": (_int, [_vp, _vp]),
     "hm_graph_export": (_int, [_vp, _int, _vp]),
     "count_exact": (_int, [_vp, _int, _vp, _vp]),
+    "count_exact_many": (_int, [_int, _vp, _vp, _vp, _vp, _vp, _int, _int, _vp, _int, _vp]),
     "count_exact_noalloc": (_int, [_vp, _int, _vp, _vp]),
     "count_baseline": (_int, [_vp, _int, _vp, _vp, _vp]),
     "hm_sample_sizes": (_int, [_vp, _int, _dbl, _int, _vp]),
@@ -242,6 +243,34 @@ def count_exact(H: Graph, k: int, out=None, stream=None):
     if out is None:
         out = torch.empty(n, dtype=torch.int64, device="cuda")
     _check(lib().count_exact(H.handle, k, ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)))
+    return out
+
+
+def count_exact_many(graphs, k: int, workers: int = 3, out=None, stream=None):
+    """Exact per-class counts of many hypergraphs in one call.  graphs: a
+    sequence of (members, offsets, n_nodes), members/offsets CUDA torch tensors
+    (int32 / int64).  Returns an int64 tensor of len(graphs) x classes."""
+    import torch
+    n = len(graphs)
+    C = hm_num_classes(k)
+    if out is None:
+        out = torch.empty((n, C), dtype=torch.int64, device="cuda")
+    keep = []
+    mp, op = (ctypes.c_void_p * max(n, 1))(), (ctypes.c_void_p * max(n, 1))()
+    ne, nm = (ctypes.c_uint64 * max(n, 1))(), (ctypes.c_uint64 * max(n, 1))()
+    nn = (ctypes.c_uint32 * max(n, 1))()
+    seen = {}   # a tensor pair given several times is converted once
+    for g, (members, offsets, n_nodes) in enumerate(graphs):
+        key = (id(members), id(offsets))
+        if key not in seen:
+            m = members.to(torch.int32).contiguous()
+            o = offsets.to(torch.int64).contiguous()
+            keep += [m, o]
+            seen[key] = (m.data_ptr(), o.data_ptr(), o.numel() - 1, m.numel())
+        mp[g], op[g], ne[g], nm[g] = seen[key]
+        nn[g] = n_nodes
+    _check(lib().count_exact_many(n, mp, op, ne, nm, nn, HM_MEM_DEVICE, k, ctypes.c_void_p(out.data_ptr()), workers,
+                                  _stream_ptr(stream)))
     return out
 
 

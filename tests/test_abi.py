@@ -63,6 +63,15 @@ def test_null_arguments_are_refused_before_the_device():
     assert lib.count_baseline(None, 4, buf, buf, None) == hm.binding.HM_EINVAL
     assert lib.count_baseline(None, 4, None, None, None) == hm.binding.HM_EINVAL
     assert lib.count_exact(None, 4, buf, None) == hm.binding.HM_EINVAL
+    # count_exact_many: counts, workers and order are checked before any HIP call
+    E, U = hm.binding.HM_EINVAL, hm.binding.HM_EUNSUPPORTED
+    assert lib.count_exact_many(-1, None, None, None, None, None, 1, 4, None, 3, None) == E
+    assert lib.count_exact_many(2, None, None, None, None, None, 1, 4, None, 0, None) == E
+    assert lib.count_exact_many(2, None, None, None, None, None, 1, 4, None, 17, None) == E
+    assert lib.count_exact_many(2, None, None, None, None, None, 1, 5, None, 3, None) == U
+    assert lib.count_exact_many(2, None, None, None, None, None, 1, 4, None, 3, None) == E
+    assert "NULL" in hm.lib().hm_last_error().decode()
+    assert lib.count_exact_many(0, None, None, None, None, None, 1, 4, None, 3, None) == hm.binding.HM_OK
 
 
 def test_options_host_logic():

@@ -505,3 +505,52 @@ def test_invalid_input_then_valid_same_size(hm):
             hm.hm_graph_create(bad, h.offsets, h.n_nodes)
         with hm.hm_graph_create(h.members, h.offsets, h.n_nodes) as g:
             assert np.array_equal(hm.count_exact(g, 4).cpu().numpy(), want)
+
+
+def _device_graphs(hs):
+    import torch
+    dev = torch.device("cuda:0")
+    return [(torch.from_numpy(h.members.astype(np.int32)).to(dev), torch.from_numpy(h.offsets.astype(np.int64)).to(dev),
+             h.n_nodes) for h in hs]
+
+
+@pytest.mark.parametrize("workers", [1, 3, 8])
+def test_count_exact_many_matches_oracle(hm, workers):
+    """Many hypergraphs in one call, shared among worker threads with a
+    stream each: every row equals the oracle's counts of its hypergraph
+    (different sizes, repeated hyperedges and singletons)."""
+    hs = [W.random_small(900 + s, 10 + 9 * s, 40 + 50 * s, {1: 0.05, 2: 0.45, 3: 0.3, 4: 0.15, 5: 0.05},
+                         allow_dups=True) for s in range(12)]
+    graphs = _device_graphs(hs)
+    for k in (3, 4):
+        got = hm.count_exact_many(graphs, k, workers=workers).cpu().numpy()
+        assert got.shape == (len(hs), hm.hm_num_classes(k))
+        for g, h in enumerate(hs):
+            assert np.array_equal(got[g], core.count_exact(h, k)), (k, g)
+
+
+def test_count_exact_many_benchmark_workload(hm):
+    """The benchmark's workload 24 times over in one call, three workers:
+    every row equals the stored oracle counts."""
+    h = W.cfg1_facetoface_k4(0)
+    got = hm.count_exact_many(_device_graphs([h]) * 24, 4, workers=3).cpu().numpy()
+    want = _golden("facetoface_N400_E30000", 4)
+    for g in range(24):
+        assert np.array_equal(got[g], want), g
+
+
+@pytest.mark.parametrize("workers", [1, 3])
+def test_count_exact_many_reports_the_failing_graph(hm, workers):
+    """An invalid hypergraph among valid ones: the call fails with the
+    hypergraph's index and its validation message, and the next call on valid
+    input counts as before."""
+    good = W.random_small(31, 30, 200, {2: 0.5, 3: 0.3, 4: 0.2}, allow_dups=True)
+    bad_members = good.members.copy()
+    bad_members[7] = good.n_nodes
+    bad = W.Hypergraph(good.n_nodes, bad_members, good.offsets)
+    graphs = _device_graphs([good, good, good, bad, good, good])
+    with pytest.raises(hm.HMError, match="hypergraph 3: .*node id"):
+        hm.count_exact_many(graphs, 4, workers=workers)
+    got = hm.count_exact_many(_device_graphs([good] * 4), 4, workers=workers).cpu().numpy()
+    for g in range(4):
+        assert np.array_equal(got[g], core.count_exact(good, 4))
