@@ -332,6 +332,44 @@ def large_workloads(hm, W, torch, seeds: int = 32, exact_only: bool = False) -> 
     return out
 
 
+def order5_leg(hm, W, stream):
+    """Order 5 (Section 6.4 samples at order 5) on the communication recipe
+    at 0.004 of its size (N=200, hyperedges of sizes 2..5: a pair sample
+    enumerates about 10^6 candidate sets, the dense face-to-face graph 10^7):
+    the exact counts from the census (every hyperedge of size 2..5 drawn once,
+    whose estimate is the exact count of every class), then sampled estimates
+    at 1, 5 and 10% of every stratum over 16 seeds, with the mean relative
+    error of the order-4 rows."""
+    h5 = W.scaled_communication(0.004)
+    g5 = hm.hm_graph_create(h5.members, h5.offsets, h5.n_nodes, stream=stream)
+    sizes5 = hm.hm_order5_sizes(g5, stream=stream)
+    everyone = {j: np.arange(sizes5[j]) for j in (2, 3, 4, 5)}
+    hm.count_sampled5(g5, 0.01, 999, stream=stream)   # untimed: first-call set-up
+    t0 = time.perf_counter()
+    c_can, _, c_est = hm.count_sampled5_indices(g5, everyone, stream=stream)
+    census_ms = (time.perf_counter() - t0) * 1e3
+    exact5 = dict(zip(c_can.tolist(), c_est.astype(np.float64).tolist()))
+    total5 = sum(exact5.values())
+    rows5 = {}
+    for f in (0.01, 0.05, 0.10):
+        outs = []
+        t0 = time.perf_counter()
+        for seed in range(16):
+            can, _, est = hm.count_sampled5(g5, f, 2000 + seed, stream=stream)
+            outs.append(dict(zip(can.tolist(), est.astype(np.float64).tolist())))
+        ms5 = (time.perf_counter() - t0) * 1e3 / 16
+        errs = []
+        for got in outs:
+            keys = set(exact5) | set(got)
+            errs.append(sum(abs(got.get(c, 0.0) - exact5.get(c, 0.0)) for c in keys) / total5)
+        rows5[f"{f:g}"] = {"ms": ms5, "mre": float(np.mean(errs)), "speedup_vs_census": census_ms / ms5}
+    g5.close()
+    order5 = {"workload": "communication_scaled_0.004_N200", "classes": len(exact5),
+              "connected_5_sets": total5, "census_ms": census_ms, "hyperedges_by_size": sizes5,
+              "sampled": rows5, "timing": "host clock per call, results copied back"}
+    return order5
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -347,6 +385,8 @@ def main() -> int:
     ap.add_argument("--learned-only", action="store_true",
                     help="only train the learned proposal on the communication workload's 5%% subsample and draw "
                          "8 learned estimates at 0.15%% (for a kernel trace of the learned path)")
+    ap.add_argument("--order5-only", action="store_true",
+                    help="only the order-5 leg (census and sampled estimates), for profiling")
     ap.add_argument("--nulls-only", action="store_true",
                     help="only the 64-copy stub-matching null batch of the face-to-face workload: the first call "
                          "(tuning and capture) and 5 replays (for a kernel trace of the null pipeline)")
@@ -392,6 +432,9 @@ def main() -> int:
         return 0
     if args.lookup_only:
         print(json.dumps({"large_workloads": large_workloads(hm, W, torch, exact_only=True)}))
+        return 0
+    if args.order5_only:
+        print(json.dumps({"order5": order5_leg(hm, W, torch.cuda.current_stream())}))
         return 0
     if args.nulls_only:
         h = W.cfg1_facetoface_k4(0)
@@ -533,42 +576,7 @@ def main() -> int:
     ok = [k for k, v in sampled.items() if v["mre"] <= 0.02]
     best = min(ok, key=lambda k: float(k)) if ok else None
 
-    # order 5 (Section 6.4 samples at order 5) on the communication recipe
-    # at 0.004 of its size (N=200, hyperedges of sizes 2..5: a pair sample
-    # enumerates about 10^6 candidate sets, the dense face-to-face graph
-    # 10^7): the exact counts from the census (every hyperedge of size 2..5
-    # drawn once, whose estimate is the exact count of every class), then
-    # sampled estimates at 1, 5 and 10% of every stratum over 16 seeds, with
-    # the same mean relative error as above
-    order5 = None
-    if not args.exact_only:
-        h5 = W.scaled_communication(0.004)
-        g5 = hm.hm_graph_create(h5.members, h5.offsets, h5.n_nodes, stream=stream)
-        sizes5 = hm.hm_order5_sizes(g5, stream=stream)
-        everyone = {j: np.arange(sizes5[j]) for j in (2, 3, 4, 5)}
-        hm.count_sampled5(g5, 0.01, 999, stream=stream)   # untimed: first-call set-up
-        t0 = time.perf_counter()
-        c_can, _, c_est = hm.count_sampled5_indices(g5, everyone, stream=stream)
-        census_ms = (time.perf_counter() - t0) * 1e3
-        exact5 = dict(zip(c_can.tolist(), c_est.astype(np.float64).tolist()))
-        total5 = sum(exact5.values())
-        rows5 = {}
-        for f in (0.01, 0.05, 0.10):
-            outs = []
-            t0 = time.perf_counter()
-            for seed in range(16):
-                can, _, est = hm.count_sampled5(g5, f, 2000 + seed, stream=stream)
-                outs.append(dict(zip(can.tolist(), est.astype(np.float64).tolist())))
-            ms5 = (time.perf_counter() - t0) * 1e3 / 16
-            errs = []
-            for got in outs:
-                keys = set(exact5) | set(got)
-                errs.append(sum(abs(got.get(c, 0.0) - exact5.get(c, 0.0)) for c in keys) / total5)
-            rows5[f"{f:g}"] = {"ms": ms5, "mre": float(np.mean(errs)), "speedup_vs_census": census_ms / ms5}
-        g5.close()
-        order5 = {"workload": "communication_scaled_0.004_N200", "classes": len(exact5),
-                  "connected_5_sets": total5, "census_ms": census_ms, "hyperedges_by_size": sizes5,
-                  "sampled": rows5, "timing": "host clock per call, results copied back"}
+    order5 = None if args.exact_only else order5_leg(hm, W, stream)
 
     # Section 6.3 and Table 3: motif profiles against 10 configuration-model
     # draws (counted exactly), and the accuracy of profiles whose observed
