@@ -554,18 +554,44 @@ __global__ void __launch_bounds__(kTile) k_gather_tiles(const uint32_t* __restri
                                       g.n, g.deg.R, part[0]);
     return;
   }
+  // The hyperedge's flags and, for a first occurrence, its first four
+  // members go out before the tile counters are summed, so that their round
+  // trips overlap (the rest of a larger hyperedge is read later, one by one).
+  const uint64_t i = uint64_t(blockIdx.x) * kTile + threadIdx.x;
+  uint32_t first = 0, s = 0;
+  uint64_t at = 0;   // the hyperedge's members in sm
+  unsigned long long so = 0;
+  if (i < n_edges) {
+    first = first_in[i];
+    s = size[i];
+    at = off[i];
+    if (g.dedup_clear) so = g.slot_of[i];   // (meaningful when first)
+  }
+  uint32_t mm[4];
+#pragma unroll
+  for (uint32_t j = 0; j < 4; ++j) mm[j] = first && j < s ? sm[at + j] : 0u;
   if (g.self_offsets) {
-    const DevFlags f = tile_flags(tile_off, threadIdx.x, n_tiles, kTile);
+    // every counter of the tiles a thread takes in one round of loads: the
+    // five position counters, and the validation summary (singletons,
+    // repeats, error bits, first erroneous index)
+    __shared__ uint32_t fred[4][kTile / kWave];
     uint32_t before[kTileN], all[kTileN];
 #pragma unroll
     for (int k = 0; k < kTileN; ++k) before[k] = all[k] = 0;
+    uint32_t sg = 0, dp = 0, er = 0, mn = 0xFFFFFFFFu;
     for (uint64_t t = threadIdx.x; t < n_tiles; t += kTile) {
+      uint32_t x[kTileS];
+#pragma unroll
+      for (int k = 0; k < kTileS; ++k) x[k] = tile_off[t * kTileS + k];
 #pragma unroll
       for (int k = 0; k < kTileN; ++k) {
-        const uint32_t x = tile_off[t * kTileS + k];
-        all[k] += x;
-        if (t < blockIdx.x) before[k] += x;
+        all[k] += x[k];
+        if (t < blockIdx.x) before[k] += x[k];
       }
+      sg += x[kTSingles];
+      dp += x[kTDups];
+      er |= x[kTErr];
+      mn = min(mn, x[kTErrMin]);
     }
 #pragma unroll
     for (int k = 0; k < kTileN; ++k) {
@@ -575,7 +601,31 @@ __global__ void __launch_bounds__(kTile) k_gather_tiles(const uint32_t* __restri
         red[kTileN + k][wv] = a;
       }
     }
+    sg = wave_sum_u32(sg);
+    dp = wave_sum_u32(dp);
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) {
+      er |= __shfl_xor(er, o, kWave);
+      mn = min(mn, uint32_t(__shfl_xor(mn, o, kWave)));
+    }
+    if (lane == 0) {
+      fred[0][wv] = sg;
+      fred[1][wv] = dp;
+      fred[2][wv] = er;
+      fred[3][wv] = mn;
+    }
     __syncthreads();
+    DevFlags f;
+    f.singletons = 0;
+    f.duplicates = 0;
+    f.err = 0;
+    f.err_edge = 0xFFFFFFFFu;
+    for (int q = 0; q < kTile / kWave; ++q) {
+      f.singletons += fred[0][q];
+      f.duplicates += fred[1][q];
+      f.err |= fred[2][q];
+      f.err_edge = min(f.err_edge, fred[3][q]);
+    }
     if (threadIdx.x < 2 * kTileN) {
       uint32_t x = 0;
       for (int q = 0; q < kTile / kWave; ++q) x += red[threadIdx.x][q];
@@ -608,16 +658,6 @@ __global__ void __launch_bounds__(kTile) k_gather_tiles(const uint32_t* __restri
     __syncthreads();
   }
   if (bad) return;
-  const uint64_t i = uint64_t(blockIdx.x) * kTile + threadIdx.x;
-  uint32_t first = 0, s = 0;
-  uint64_t at = 0;   // the hyperedge's members in sm (loaded with its flags)
-  unsigned long long so = 0;
-  if (i < n_edges) {
-    first = first_in[i];
-    s = size[i];
-    at = off[i];
-    if (g.dedup_clear) so = g.slot_of[i];   // (meaningful when first)
-  }
   uint32_t t[kTileN];
   tile_terms(first, s, t);
   uint32_t pre[kTileN];
@@ -636,11 +676,6 @@ __global__ void __launch_bounds__(kTile) k_gather_tiles(const uint32_t* __restri
     pos[k] = p;
   }
   const uint32_t* m = sm + at;
-  // the first four members, loaded at once (the rest of a larger hyperedge
-  // one by one)
-  uint32_t mm[4];
-#pragma unroll
-  for (uint32_t j = 0; j < 4; ++j) mm[j] = j < s ? m[j] : 0u;
 #pragma unroll
   for (uint32_t j = 0; j < 4; ++j)
     if (j < s) g.all_members[pos[4] + j] = mm[j];
