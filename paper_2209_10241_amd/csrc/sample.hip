@@ -794,32 +794,62 @@ __device__ void sample_j2_k4_bits(const View& v, const Draws& d, uint32_t part, 
     if (i >= d.n[2]) continue;
     unsigned long long* h = row_or(rows, s, h_lds);
     const uint32_t u = v.e2[2 * i], w = v.e2[2 * i + 1];
+    // the rows of u and w and the bounds of the three incidence lists the
+    // sample walks go out together
     if (tid < W) {
       L.RU[tid] = bits[uint64_t(u) * W + tid];
       L.RW[tid] = bits[uint64_t(w) * W + tid];
       L.XS[tid] = 0;
     }
     if (tid < 21) L.red[tid] = 0;
+    const uint32_t u0 = v.i3_off[u], u1 = v.i3_off[u + 1];
+    const uint32_t w0 = v.i3_off[w], w1 = v.i3_off[w + 1];
+    const uint32_t f0 = v.i4_off[u], f1 = v.i4_off[u + 1];
+    // Each list's first kThreads entries, one per thread, in one round (each
+    // entry carries the hyperedge's other members, ascending), and from them
+    // the pairs {x, y} the second term (below) removes, with the probes that
+    // decide it and the pair bit of x, y, before the first barrier: an
+    // entry of u's 3-node hyperedges without w (cand 0), of w's without u
+    // whose set is not a 3-node hyperedge at u (cand 1), and of u's 4-node
+    // hyperedges holding w whose other two members close no 3-node
+    // hyperedge with u or w (cand 2).
+    const bool has_u = u0 + tid < u1, has_w = w0 + tid < w1, has_f = f0 + tid < f1;
+    const uint32_t ou = has_u ? v.i3_oth[u0 + tid] : 0u;
+    const uint32_t ow = has_w ? v.i3_oth[w0 + tid] : 0u;
+    const unsigned long long of = has_f ? v.i4_oth[f0 + tid] : 0ull;
+    uint32_t cx[3], cy[3], cb[3];
+    bool cand[3];
+    cx[0] = ou & 0xFFFFu;
+    cy[0] = ou >> 16;
+    cand[0] = has_u && cx[0] != w && cy[0] != w;
+    cx[1] = ow & 0xFFFFu;
+    cy[1] = ow >> 16;
+    cand[1] = has_w && cx[1] != u && cy[1] != u;
+    {
+      const uint32_t a = uint32_t(of) & 0xFFFFu, b = uint32_t(of >> 16) & 0xFFFFu, c = uint32_t(of >> 32) & 0xFFFFu;
+      cand[2] = has_f && (a == w || b == w || c == w);
+      cx[2] = a == w ? b : a;
+      cy[2] = c == w ? b : c;
+    }
+    if (cand[1] && has3(v.hs3, u, cx[1], cy[1])) cand[1] = false;   // taken at u
+    if (cand[2] && (has3(v.hs3, u, cx[2], cy[2]) || has3(v.hs3, w, cx[2], cy[2]))) cand[2] = false;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) cb[c] = cand[c] ? uint32_t(bit_of(bits, W, cx[c], cy[c])) : 0u;
     __syncthreads();
     if (tid == 0) {
       atomicOr(&L.XS[u >> 5], 1u << (u & 31));
       atomicOr(&L.XS[w >> 5], 1u << (w & 31));
     }
-    const uint32_t u0 = v.i3_off[u], u1 = v.i3_off[u + 1];
-    // the 3-node hyperedges at u: those holding w give T; when there are at
-    // most kThreads of them, each thread keeps the other pair of its own for
-    // the second term (below) instead of reading it again
-    const bool one_round = u1 - u0 <= kThreads;
-    uint32_t own_x = 0xFFFFFFFFu, own_y = 0xFFFFFFFFu;
-    // (each entry carries the hyperedge's other two members, ascending)
-    for (uint32_t p = u0 + tid; p < u1; p += kThreads) {
+    // the 3-node hyperedges at u holding w give T
+    if (has_u && !cand[0]) {
+      const uint32_t c = cx[0] ^ cy[0] ^ w;
+      atomicOr(&L.XS[c >> 5], 1u << (c & 31));
+    }
+    for (uint32_t p = u0 + tid + kThreads; p < u1; p += kThreads) {
       const uint32_t o = v.i3_oth[p], y = o & 0xFFFFu, z = o >> 16;
       if (y == w || z == w) {
         const uint32_t c = y ^ z ^ w;
         atomicOr(&L.XS[c >> 5], 1u << (c & 31));
-      } else {
-        own_x = y;
-        own_y = z;
       }
     }
     __syncthreads();
@@ -884,32 +914,31 @@ __device__ void sample_j2_k4_bits(const View& v, const Draws& d, uint32_t part, 
           for (int j = 0; j < 7; ++j) acc[c][j] += xc == uint32_t(c + 1) ? c7[j] : 0u;
       }
     }
-    // second term: each pair {x, y} outside X whose set holds a larger hyperedge
-    auto remove = [&](uint32_t x, uint32_t y) {
+    // second term: each pair {x, y} outside X whose set holds a larger
+    // hyperedge (pb: the pair bit of x, y)
+    auto remove = [&](uint32_t x, uint32_t y, uint32_t pb) {
       if (node_bit(L.XS, x) | node_bit(L.XS, y)) return;
       const uint32_t pat = 1u | (node_bit(L.RU, x) << 1) | (node_bit(L.RW, x) << 2) | (node_bit(L.RU, y) << 4) |
-                           (node_bit(L.RW, y) << 5) | (bit_of(bits, W, x, y) << 7);
+                           (node_bit(L.RW, y) << 5) | (pb << 7);
       const uint8_t cls = lut[pat];
       if (cls != 0xFF) atomicAdd(&h[cls], ~0ull);   // minus one
     };
-    if (one_round) {
-      if (own_x != 0xFFFFFFFFu) remove(own_x, own_y);
-    } else {
-      for (uint32_t p = u0 + tid; p < u1; p += kThreads) {
-        const uint32_t o = v.i3_oth[p], y = o & 0xFFFFu, z = o >> 16;
-        if (y == w || z == w) continue;
-        remove(y, z);
-      }
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+      if (cand[c]) remove(cx[c], cy[c], cb[c]);
+    // (entries past each list's first kThreads)
+    for (uint32_t p = u0 + tid + kThreads; p < u1; p += kThreads) {
+      const uint32_t o = v.i3_oth[p], y = o & 0xFFFFu, z = o >> 16;
+      if (y == w || z == w) continue;
+      remove(y, z, bit_of(bits, W, y, z));
     }
-    const uint32_t w0 = v.i3_off[w], w1 = v.i3_off[w + 1];
-    for (uint32_t p = w0 + tid; p < w1; p += kThreads) {
+    for (uint32_t p = w0 + tid + kThreads; p < w1; p += kThreads) {
       const uint32_t o = v.i3_oth[p], x = o & 0xFFFFu, y = o >> 16;   // w's hyperedge {w, x, y}
       if (x == u || y == u) continue;
       if (has3(v.hs3, u, x, y)) continue;   // taken at u
-      remove(x, y);
+      remove(x, y, bit_of(bits, W, x, y));
     }
-    const uint32_t f0 = v.i4_off[u], f1 = v.i4_off[u + 1];
-    for (uint32_t p = f0 + tid; p < f1; p += kThreads) {
+    for (uint32_t p = f0 + tid + kThreads; p < f1; p += kThreads) {
       // u's hyperedge {u, a, b, c}, a < b < c
       const unsigned long long o = v.i4_oth[p];
       const uint32_t a = uint32_t(o) & 0xFFFFu, b = uint32_t(o >> 16) & 0xFFFFu, c = uint32_t(o >> 32) & 0xFFFFu;
@@ -917,7 +946,7 @@ __device__ void sample_j2_k4_bits(const View& v, const Draws& d, uint32_t part, 
       // the two members other than u and w, ascending
       const uint32_t x = a == w ? b : a, y = c == w ? b : c;
       if (has3(v.hs3, u, x, y) || has3(v.hs3, w, x, y)) continue;   // taken at u or w
-      remove(x, y);
+      remove(x, y, bit_of(bits, W, x, y));
     }
 #pragma unroll
     for (int c = 0; c < 3; ++c)
