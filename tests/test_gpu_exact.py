@@ -554,3 +554,28 @@ def test_count_exact_many_reports_the_failing_graph(hm, workers):
     got = hm.count_exact_many(_device_graphs([good] * 4), 4, workers=workers).cpu().numpy()
     for g in range(4):
         assert np.array_equal(got[g], core.count_exact(good, 4))
+
+
+def test_count_exact_many_host_memory(hm):
+    """count_exact_many with the hypergraphs in host memory (HM_MEM_HOST),
+    called through the C ABI: each worker copies its graphs' arrays to the
+    device on its own stream; every row equals the oracle's counts."""
+    import ctypes
+    import torch
+    hs = [W.random_small(700 + s, 15 + 7 * s, 60 + 40 * s, {2: 0.5, 3: 0.3, 4: 0.2}, allow_dups=True)
+          for s in range(9)]
+    n = len(hs)
+    C = hm.hm_num_classes(4)
+    out = torch.empty((n, C), dtype=torch.int64, device="cuda")
+    mp, op = (ctypes.c_void_p * n)(), (ctypes.c_void_p * n)()
+    ne, nm, nn = (ctypes.c_uint64 * n)(), (ctypes.c_uint64 * n)(), (ctypes.c_uint32 * n)()
+    for g, h in enumerate(hs):
+        mp[g], op[g] = h.members.ctypes.data, h.offsets.ctypes.data
+        ne[g], nm[g], nn[g] = h.n_edges, len(h.members), h.n_nodes
+    st = torch.cuda.current_stream()
+    rc = hm.lib().count_exact_many(n, mp, op, ne, nm, nn, hm.binding.HM_MEM_HOST, 4, ctypes.c_void_p(out.data_ptr()),
+                                   4, ctypes.c_void_p(st.cuda_stream))
+    assert rc == 0, hm.lib().hm_last_error().decode()
+    got = out.cpu().numpy()
+    for g, h in enumerate(hs):
+        assert np.array_equal(got[g], core.count_exact(h, 4)), g
