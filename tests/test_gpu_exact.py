@@ -521,6 +521,10 @@ def test_count_exact_many_matches_oracle(hm, workers):
     (different sizes, repeated hyperedges and singletons)."""
     hs = [W.random_small(900 + s, 10 + 9 * s, 40 + 50 * s, {1: 0.05, 2: 0.45, 3: 0.3, 4: 0.15, 5: 0.05},
                          allow_dups=True) for s in range(12)]
+    # and the degenerate cases: no hyperedge, singletons only, one pair
+    hs += [W.Hypergraph(7, np.zeros(0, np.uint32), np.zeros(1, np.uint64)),
+           W.Hypergraph(5, np.array([0, 3, 4], np.uint32), np.array([0, 1, 2, 3], np.uint64)),
+           W.Hypergraph(4, np.array([1, 2], np.uint32), np.array([0, 2], np.uint64))]
     graphs = _device_graphs(hs)
     for k in (3, 4):
         got = hm.count_exact_many(graphs, k, workers=workers).cpu().numpy()
