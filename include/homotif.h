@@ -142,8 +142,9 @@ int count_exact(const hm_graph* H, int k, int64_t* counts, void* stream);
  * gives them (members and offsets in the memory mem_kind names; the five
  * arrays of n_graphs entries are host memory), and its counts go to
  * counts[g * hm_num_classes(k) ...] (device, overwritten).  The hypergraphs
- * are shared among `workers` host threads (1..16), each building, counting
- * and releasing its graphs on a stream of its own (the library keeps these
+ * are shared among `workers` host threads (1..16: the calling thread and up
+ * to workers - 1 that it starts), each building, counting and releasing its
+ * graphs on a stream of its own (the library keeps these
  * streams per device for the process), so that one graph's build, which
  * waits for its validation on the host, runs beside another's count.  The
  * workers start after the work already enqueued on `stream`, and `stream`

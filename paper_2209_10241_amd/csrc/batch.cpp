@@ -9,8 +9,8 @@
 
 #include <algorithm>
 #include <atomic>
+#include <cstdio>
 #include <mutex>
-#include <string>
 #include <thread>
 #include <vector>
 
@@ -28,14 +28,20 @@ std::vector<std::vector<hipStream_t>> g_worker_streams;
 
 int worker_streams(int device, int n, hipStream_t* out) {
   std::lock_guard<std::mutex> lock(g_worker_mu);
-  if (size_t(device) >= g_worker_streams.size()) g_worker_streams.resize(size_t(device) + 1);
-  auto& v = g_worker_streams[size_t(device)];
-  while (int(v.size()) < n) {
-    hipStream_t s = nullptr;
-    HM_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
-    v.push_back(s);
+  try {
+    if (size_t(device) >= g_worker_streams.size()) g_worker_streams.resize(size_t(device) + 1);
+    auto& v = g_worker_streams[size_t(device)];
+    v.reserve(kMaxWorkers);
+    while (int(v.size()) < n) {
+      hipStream_t s = nullptr;
+      HM_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+      v.push_back(s);
+    }
+    for (int t = 0; t < n; ++t) out[t] = v[size_t(t)];
+  } catch (...) {
+    set_error("host allocation failed");
+    return HM_ENOMEM;
   }
-  for (int t = 0; t < n; ++t) out[t] = v[size_t(t)];
   return HM_OK;
 }
 
@@ -84,13 +90,18 @@ extern "C" int count_exact_many(int n_graphs, const uint32_t* const* members, co
 
   std::atomic<int> next{0};
   std::atomic<bool> stop{false};
-  std::vector<int> rc(size_t(T), HM_OK), failed(size_t(T), -1);
-  std::vector<std::string> msg(static_cast<size_t>(T));
+  int rc[hm::kMaxWorkers], failed[hm::kMaxWorkers];
+  char msg[hm::kMaxWorkers][512];
+  for (int t = 0; t < T; ++t) {
+    rc[t] = HM_OK;
+    failed[t] = -1;
+    msg[t][0] = 0;
+  }
   auto work = [&](int t) {
     if (hipSetDevice(device) != hipSuccess) {
-      rc[size_t(t)] = HM_EDEVICE;
-      failed[size_t(t)] = -1;
-      msg[size_t(t)] = "hipSetDevice failed in a worker thread";
+      rc[t] = HM_EDEVICE;
+      failed[t] = -1;
+      std::snprintf(msg[t], sizeof(msg[t]), "hipSetDevice failed in a worker thread");
       stop = true;
       return;
     }
@@ -100,34 +111,40 @@ extern "C" int count_exact_many(int n_graphs, const uint32_t* const* members, co
       hm_graph* H = nullptr;
       int r = hm_graph_create(members[g], offsets[g], n_edges[g], n_members[g], n_nodes[g], mem_kind, ws[t], &H);
       if (r == HM_OK) r = count_exact(H, k, counts + int64_t(g) * C, ws[t]);
-      if (r != HM_OK) msg[size_t(t)] = hm_last_error();
+      if (r != HM_OK) std::snprintf(msg[t], sizeof(msg[t]), "%s", hm_last_error());
       if (H) (void)hm_graph_destroy(H);
       if (r != HM_OK) {
-        rc[size_t(t)] = r;
-        failed[size_t(t)] = g;
+        rc[t] = r;
+        failed[t] = g;
         stop = true;
         return;
       }
     }
   };
+  // the calling thread is worker 0; a worker thread that cannot be started
+  // leaves its share to the others (the graphs are taken from one counter)
   std::vector<std::thread> threads;
-  threads.reserve(size_t(T));
-  for (int t = 0; t < T; ++t) threads.emplace_back(work, t);
+  try {
+    threads.reserve(size_t(T));
+    for (int t = 1; t < T; ++t) threads.emplace_back(work, t);
+  } catch (...) {
+  }
+  work(0);
   for (auto& th : threads) th.join();
 
   // the lowest failing graph among those attempted
   int worst = -1;
   for (int t = 0; t < T; ++t)
-    if (rc[size_t(t)] != HM_OK && (worst < 0 || failed[size_t(t)] < failed[size_t(worst)])) worst = t;
+    if (rc[t] != HM_OK && (worst < 0 || failed[t] < failed[worst])) worst = t;
   // `stream` waits for every worker's work, also after a failure (the
   // caller's buffers stay in use until then)
   const int jr = hm::join_streams(ws, T, caller);
   if (worst >= 0) {
-    if (failed[size_t(worst)] >= 0)
-      hm::set_error("hypergraph %d: %s", failed[size_t(worst)], msg[size_t(worst)].c_str());
+    if (failed[worst] >= 0)
+      hm::set_error("hypergraph %d: %s", failed[worst], msg[worst]);
     else
-      hm::set_error("%s", msg[size_t(worst)].c_str());
-    return rc[size_t(worst)];
+      hm::set_error("%s", msg[worst]);
+    return rc[worst];
   }
   return jr;
 }
