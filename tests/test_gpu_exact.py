@@ -583,3 +583,18 @@ def test_count_exact_many_host_memory(hm):
     got = out.cpu().numpy()
     for g, h in enumerate(hs):
         assert np.array_equal(got[g], core.count_exact(h, 4)), g
+
+
+def test_count_exact_many_repeats_the_duplicate_search(hm):
+    """With no tag bits every build's one-launch duplicate search meets
+    different hyperedges and is repeated exactly, here inside the worker
+    threads of count_exact_many: the rows still equal the oracle's counts."""
+    hs = [W.random_small(610 + s, 25 + 5 * s, 150 + 40 * s, {1: 0.05, 2: 0.5, 3: 0.3, 4: 0.15}, allow_dups=True)
+          for s in range(6)]
+    hm.hm_set_option(hm.HM_OPT_DEDUP_TAG_BITS, 0)
+    try:
+        got = hm.count_exact_many(_device_graphs(hs), 4, workers=3).cpu().numpy()
+    finally:
+        hm.hm_set_option(hm.HM_OPT_DEDUP_TAG_BITS, 32)
+    for g, h in enumerate(hs):
+        assert np.array_equal(got[g], core.count_exact(h, 4)), g
