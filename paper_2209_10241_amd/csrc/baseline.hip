@@ -244,14 +244,18 @@ int count_baseline_impl(const hm_graph* H, int k, int64_t* counts, unsigned long
 }  // namespace hm
 
 extern "C" int count_baseline(const hm_graph* H, int k, int64_t* counts, uint64_t* stats, void* stream) {
-  if (!H || !counts || !stats) {
-    hm::set_error("NULL argument to count_baseline");
-    return HM_EINVAL;
+  try {
+    if (!H || !counts || !stats) {
+      hm::set_error("NULL argument to count_baseline");
+      return HM_EINVAL;
+    }
+    if (k != 3 && k != 4) {
+      hm::set_error("order %d is not supported (3 or 4)", k);
+      return HM_EUNSUPPORTED;
+    }
+    return hm::count_baseline_impl(H, k, counts, reinterpret_cast<unsigned long long*>(stats),
+                                   static_cast<hipStream_t>(stream));
+  } catch (...) {
+    return hm::api_failure();
   }
-  if (k != 3 && k != 4) {
-    hm::set_error("order %d is not supported (3 or 4)", k);
-    return HM_EUNSUPPORTED;
-  }
-  return hm::count_baseline_impl(H, k, counts, reinterpret_cast<unsigned long long*>(stats),
-                                 static_cast<hipStream_t>(stream));
 }

@@ -64,87 +64,91 @@ int join_streams(const hipStream_t* from, int n, hipStream_t waiter) {
 extern "C" int count_exact_many(int n_graphs, const uint32_t* const* members, const uint64_t* const* offsets,
                                 const uint64_t* n_edges, const uint64_t* n_members, const uint32_t* n_nodes,
                                 int mem_kind, int k, int64_t* counts, int workers, void* stream) {
-  if (n_graphs < 0) {
-    hm::set_error("n_graphs must not be negative");
-    return HM_EINVAL;
-  }
-  if (workers < 1 || workers > hm::kMaxWorkers) {
-    hm::set_error("workers must be in [1, %d]", hm::kMaxWorkers);
-    return HM_EINVAL;
-  }
-  const int C = hm_num_classes(k);
-  if (C < 0) return C;
-  if (n_graphs == 0) return HM_OK;
-  if (!members || !offsets || !n_edges || !n_members || !n_nodes || !counts) {
-    hm::set_error("count_exact_many: a NULL array");
-    return HM_EINVAL;
-  }
-  int device = 0;
-  HM_HIP(hipGetDevice(&device));
-  const int T = std::min(workers, n_graphs);
-  hipStream_t ws[hm::kMaxWorkers];
-  HM_TRY(hm::worker_streams(device, T, ws));
-  hipStream_t caller = static_cast<hipStream_t>(stream);
-  // the workers start after what the caller enqueued on `stream`
-  for (int t = 0; t < T; ++t) HM_TRY(hm::join_streams(&caller, 1, ws[t]));
-
-  std::atomic<int> next{0};
-  std::atomic<bool> stop{false};
-  int rc[hm::kMaxWorkers], failed[hm::kMaxWorkers];
-  char msg[hm::kMaxWorkers][512];
-  for (int t = 0; t < T; ++t) {
-    rc[t] = HM_OK;
-    failed[t] = -1;
-    msg[t][0] = 0;
-  }
-  auto work = [&](int t) {
-    if (hipSetDevice(device) != hipSuccess) {
-      rc[t] = HM_EDEVICE;
-      failed[t] = -1;
-      std::snprintf(msg[t], sizeof(msg[t]), "hipSetDevice failed in a worker thread");
-      stop = true;
-      return;
+  try {
+    if (n_graphs < 0) {
+      hm::set_error("n_graphs must not be negative");
+      return HM_EINVAL;
     }
-    while (!stop.load()) {
-      const int g = next.fetch_add(1);
-      if (g >= n_graphs) break;
-      hm_graph* H = nullptr;
-      int r = hm_graph_create(members[g], offsets[g], n_edges[g], n_members[g], n_nodes[g], mem_kind, ws[t], &H);
-      if (r == HM_OK) r = count_exact(H, k, counts + int64_t(g) * C, ws[t]);
-      if (r != HM_OK) std::snprintf(msg[t], sizeof(msg[t]), "%s", hm_last_error());
-      if (H) (void)hm_graph_destroy(H);
-      if (r != HM_OK) {
-        rc[t] = r;
-        failed[t] = g;
+    if (workers < 1 || workers > hm::kMaxWorkers) {
+      hm::set_error("workers must be in [1, %d]", hm::kMaxWorkers);
+      return HM_EINVAL;
+    }
+    const int C = hm_num_classes(k);
+    if (C < 0) return C;
+    if (n_graphs == 0) return HM_OK;
+    if (!members || !offsets || !n_edges || !n_members || !n_nodes || !counts) {
+      hm::set_error("count_exact_many: a NULL array");
+      return HM_EINVAL;
+    }
+    int device = 0;
+    HM_HIP(hipGetDevice(&device));
+    const int T = std::min(workers, n_graphs);
+    hipStream_t ws[hm::kMaxWorkers];
+    HM_TRY(hm::worker_streams(device, T, ws));
+    hipStream_t caller = static_cast<hipStream_t>(stream);
+    // the workers start after what the caller enqueued on `stream`
+    for (int t = 0; t < T; ++t) HM_TRY(hm::join_streams(&caller, 1, ws[t]));
+
+    std::atomic<int> next{0};
+    std::atomic<bool> stop{false};
+    int rc[hm::kMaxWorkers], failed[hm::kMaxWorkers];
+    char msg[hm::kMaxWorkers][512];
+    for (int t = 0; t < T; ++t) {
+      rc[t] = HM_OK;
+      failed[t] = -1;
+      msg[t][0] = 0;
+    }
+    auto work = [&](int t) {
+      if (hipSetDevice(device) != hipSuccess) {
+        rc[t] = HM_EDEVICE;
+        failed[t] = -1;
+        std::snprintf(msg[t], sizeof(msg[t]), "hipSetDevice failed in a worker thread");
         stop = true;
         return;
       }
+      while (!stop.load()) {
+        const int g = next.fetch_add(1);
+        if (g >= n_graphs) break;
+        hm_graph* H = nullptr;
+        int r = hm_graph_create(members[g], offsets[g], n_edges[g], n_members[g], n_nodes[g], mem_kind, ws[t], &H);
+        if (r == HM_OK) r = count_exact(H, k, counts + int64_t(g) * C, ws[t]);
+        if (r != HM_OK) std::snprintf(msg[t], sizeof(msg[t]), "%s", hm_last_error());
+        if (H) (void)hm_graph_destroy(H);
+        if (r != HM_OK) {
+          rc[t] = r;
+          failed[t] = g;
+          stop = true;
+          return;
+        }
+      }
+    };
+    // the calling thread is worker 0; a worker thread that cannot be started
+    // leaves its share to the others (the graphs are taken from one counter)
+    std::vector<std::thread> threads;
+    try {
+      threads.reserve(size_t(T));
+      for (int t = 1; t < T; ++t) threads.emplace_back(work, t);
+    } catch (...) {
     }
-  };
-  // the calling thread is worker 0; a worker thread that cannot be started
-  // leaves its share to the others (the graphs are taken from one counter)
-  std::vector<std::thread> threads;
-  try {
-    threads.reserve(size_t(T));
-    for (int t = 1; t < T; ++t) threads.emplace_back(work, t);
-  } catch (...) {
-  }
-  work(0);
-  for (auto& th : threads) th.join();
+    work(0);
+    for (auto& th : threads) th.join();
 
-  // the lowest failing graph among those attempted
-  int worst = -1;
-  for (int t = 0; t < T; ++t)
-    if (rc[t] != HM_OK && (worst < 0 || failed[t] < failed[worst])) worst = t;
-  // `stream` waits for every worker's work, also after a failure (the
-  // caller's buffers stay in use until then)
-  const int jr = hm::join_streams(ws, T, caller);
-  if (worst >= 0) {
-    if (failed[worst] >= 0)
-      hm::set_error("hypergraph %d: %s", failed[worst], msg[worst]);
-    else
-      hm::set_error("%s", msg[worst]);
-    return rc[worst];
+    // the lowest failing graph among those attempted
+    int worst = -1;
+    for (int t = 0; t < T; ++t)
+      if (rc[t] != HM_OK && (worst < 0 || failed[t] < failed[worst])) worst = t;
+    // `stream` waits for every worker's work, also after a failure (the
+    // caller's buffers stay in use until then)
+    const int jr = hm::join_streams(ws, T, caller);
+    if (worst >= 0) {
+      if (failed[worst] >= 0)
+        hm::set_error("hypergraph %d: %s", failed[worst], msg[worst]);
+      else
+        hm::set_error("%s", msg[worst]);
+      return rc[worst];
+    }
+    return jr;
+  } catch (...) {
+    return hm::api_failure();
   }
-  return jr;
 }

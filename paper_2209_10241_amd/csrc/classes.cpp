@@ -12,6 +12,7 @@
 #include <unordered_map>
 #include <atomic>
 #include <mutex>
+#include <new>
 #include <numeric>
 #include <vector>
 
@@ -135,6 +136,18 @@ void set_error(const char* fmt, ...) {
 }
 
 const char* last_error() { return g_err; }
+
+int api_failure() {
+  try {
+    throw;
+  } catch (const std::bad_alloc&) {
+    set_error("host allocation failed");
+    return HM_ENOMEM;
+  } catch (...) {
+    set_error("internal error: an exception reached the C ABI");
+    return HM_EINTERNAL;
+  }
+}
 
 uint32_t bitset_max_nodes() { return g_bitset_max_nodes.load(); }
 std::atomic<uint32_t> g_sample_chunk_scale{1};
@@ -362,116 +375,136 @@ const char* hm_last_error(void) { return hm::last_error(); }
 const char* hm_version(void) { return "homotif 0.1 (gfx950)"; }
 
 int hm_set_option(int option, int64_t value) {
-  if (option == HM_OPT_BITSET_MAX_NODES) {
-    if (value < 0 || value > int64_t(hm::kBitsetMaxNodes)) {
-      hm::set_error("HM_OPT_BITSET_MAX_NODES must be in [0, %u]", hm::kBitsetMaxNodes);
-      return HM_EINVAL;
+  try {
+    if (option == HM_OPT_BITSET_MAX_NODES) {
+      if (value < 0 || value > int64_t(hm::kBitsetMaxNodes)) {
+        hm::set_error("HM_OPT_BITSET_MAX_NODES must be in [0, %u]", hm::kBitsetMaxNodes);
+        return HM_EINVAL;
+      }
+      hm::g_bitset_max_nodes.store(uint32_t(value));
+      return HM_OK;
     }
-    hm::g_bitset_max_nodes.store(uint32_t(value));
-    return HM_OK;
-  }
-  if (option == HM_OPT_SAMPLE_CHUNK_SCALE) {
-    if (value < 1 || value > 1024) {
-      hm::set_error("HM_OPT_SAMPLE_CHUNK_SCALE must be in [1, 1024]");
-      return HM_EINVAL;
+    if (option == HM_OPT_SAMPLE_CHUNK_SCALE) {
+      if (value < 1 || value > 1024) {
+        hm::set_error("HM_OPT_SAMPLE_CHUNK_SCALE must be in [1, 1024]");
+        return HM_EINVAL;
+      }
+      hm::g_sample_chunk_scale.store(uint32_t(value));
+      return HM_OK;
     }
-    hm::g_sample_chunk_scale.store(uint32_t(value));
-    return HM_OK;
-  }
-  if (option == HM_OPT_ONE_PASS_MAX_EDGES) {
-    if (value < 0 || value > int64_t(hm::kOnePassMaxEdges)) {
-      hm::set_error("HM_OPT_ONE_PASS_MAX_EDGES must be in [0, %llu]", (unsigned long long)hm::kOnePassMaxEdges);
-      return HM_EINVAL;
+    if (option == HM_OPT_ONE_PASS_MAX_EDGES) {
+      if (value < 0 || value > int64_t(hm::kOnePassMaxEdges)) {
+        hm::set_error("HM_OPT_ONE_PASS_MAX_EDGES must be in [0, %llu]", (unsigned long long)hm::kOnePassMaxEdges);
+        return HM_EINVAL;
+      }
+      hm::g_one_pass_max_edges.store(uint64_t(value));
+      return HM_OK;
     }
-    hm::g_one_pass_max_edges.store(uint64_t(value));
-    return HM_OK;
-  }
-  if (option == HM_OPT_HUB_MIN_DEGREE) {
-    if (value < 0 || value > int64_t(0xFFFFFFFFu)) {
-      hm::set_error("HM_OPT_HUB_MIN_DEGREE must be in [0, 2^32 - 1]");
-      return HM_EINVAL;
+    if (option == HM_OPT_HUB_MIN_DEGREE) {
+      if (value < 0 || value > int64_t(0xFFFFFFFFu)) {
+        hm::set_error("HM_OPT_HUB_MIN_DEGREE must be in [0, 2^32 - 1]");
+        return HM_EINVAL;
+      }
+      hm::g_hub_min_degree.store(uint32_t(value));
+      return HM_OK;
     }
-    hm::g_hub_min_degree.store(uint32_t(value));
-    return HM_OK;
-  }
-  if (option == HM_OPT_DEDUP_TAG_BITS) {
-    if (value < -1 || value > 32) {
-      hm::set_error("HM_OPT_DEDUP_TAG_BITS must be in [-1, 32]");
-      return HM_EINVAL;
+    if (option == HM_OPT_DEDUP_TAG_BITS) {
+      if (value < -1 || value > 32) {
+        hm::set_error("HM_OPT_DEDUP_TAG_BITS must be in [-1, 32]");
+        return HM_EINVAL;
+      }
+      hm::g_dedup_tag_bits.store(int(value));
+      return HM_OK;
     }
-    hm::g_dedup_tag_bits.store(int(value));
-    return HM_OK;
+    hm::set_error("unknown option %d", option);
+    return HM_EINVAL;
+  } catch (...) {
+    return hm::api_failure();
   }
-  hm::set_error("unknown option %d", option);
-  return HM_EINVAL;
 }
 
 int hm_get_option(int option, int64_t* value) {
-  if (!value) {
-    hm::set_error("value is NULL");
+  try {
+    if (!value) {
+      hm::set_error("value is NULL");
+      return HM_EINVAL;
+    }
+    if (option == HM_OPT_BITSET_MAX_NODES) {
+      *value = hm::g_bitset_max_nodes.load();
+      return HM_OK;
+    }
+    if (option == HM_OPT_SAMPLE_CHUNK_SCALE) {
+      *value = hm::g_sample_chunk_scale.load();
+      return HM_OK;
+    }
+    if (option == HM_OPT_ONE_PASS_MAX_EDGES) {
+      *value = int64_t(hm::g_one_pass_max_edges.load());
+      return HM_OK;
+    }
+    if (option == HM_OPT_HUB_MIN_DEGREE) {
+      *value = int64_t(hm::g_hub_min_degree.load());
+      return HM_OK;
+    }
+    if (option == HM_OPT_DEDUP_TAG_BITS) {
+      *value = hm::g_dedup_tag_bits.load();
+      return HM_OK;
+    }
+    hm::set_error("unknown option %d", option);
     return HM_EINVAL;
+  } catch (...) {
+    return hm::api_failure();
   }
-  if (option == HM_OPT_BITSET_MAX_NODES) {
-    *value = hm::g_bitset_max_nodes.load();
-    return HM_OK;
-  }
-  if (option == HM_OPT_SAMPLE_CHUNK_SCALE) {
-    *value = hm::g_sample_chunk_scale.load();
-    return HM_OK;
-  }
-  if (option == HM_OPT_ONE_PASS_MAX_EDGES) {
-    *value = int64_t(hm::g_one_pass_max_edges.load());
-    return HM_OK;
-  }
-  if (option == HM_OPT_HUB_MIN_DEGREE) {
-    *value = int64_t(hm::g_hub_min_degree.load());
-    return HM_OK;
-  }
-  if (option == HM_OPT_DEDUP_TAG_BITS) {
-    *value = hm::g_dedup_tag_bits.load();
-    return HM_OK;
-  }
-  hm::set_error("unknown option %d", option);
-  return HM_EINVAL;
 }
 
 int hm_num_classes(int k) {
-  if (k != 3 && k != 4) {
-    hm::set_error("order %d is not supported (3 or 4)", k);
-    return HM_EUNSUPPORTED;
+  try {
+    if (k != 3 && k != 4) {
+      hm::set_error("order %d is not supported (3 or 4)", k);
+      return HM_EUNSUPPORTED;
+    }
+    return hm::class_tables().n_classes[k];
+  } catch (...) {
+    return hm::api_failure();
   }
-  return hm::class_tables().n_classes[k];
 }
 
 int hm_class_info(int k, int cls, uint32_t* canon_pattern, int* maxcard, int* countmax) {
-  int n = hm_num_classes(k);
-  if (n < 0) return n;
-  if (cls < 0 || cls >= n) {
-    hm::set_error("class %d out of range [0, %d)", cls, n);
-    return HM_EINVAL;
+  try {
+    int n = hm_num_classes(k);
+    if (n < 0) return n;
+    if (cls < 0 || cls >= n) {
+      hm::set_error("class %d out of range [0, %d)", cls, n);
+      return HM_EINVAL;
+    }
+    const hm::ClassTables& t = hm::class_tables();
+    if (canon_pattern) *canon_pattern = t.canon[k][cls];
+    if (maxcard) *maxcard = t.maxcard[k][cls];
+    if (countmax) *countmax = t.countmax[k][cls];
+    return HM_OK;
+  } catch (...) {
+    return hm::api_failure();
   }
-  const hm::ClassTables& t = hm::class_tables();
-  if (canon_pattern) *canon_pattern = t.canon[k][cls];
-  if (maxcard) *maxcard = t.maxcard[k][cls];
-  if (countmax) *countmax = t.countmax[k][cls];
-  return HM_OK;
 }
 
 int hm_pattern_class(int k, uint32_t pattern, int* cls) {
-  int n = hm_num_classes(k);
-  if (n < 0) return n;
-  if (!cls) {
-    hm::set_error("cls is NULL");
-    return HM_EINVAL;
+  try {
+    int n = hm_num_classes(k);
+    if (n < 0) return n;
+    if (!cls) {
+      hm::set_error("cls is NULL");
+      return HM_EINVAL;
+    }
+    const hm::ClassTables& t = hm::class_tables();
+    if (pattern >= (k == 3 ? 16u : 2048u)) {
+      hm::set_error("pattern %u out of range for order %d", pattern, k);
+      return HM_EINVAL;
+    }
+    uint8_t c = (k == 3) ? t.lut3[pattern] : t.lut4[pattern];
+    *cls = c == 0xFF ? -1 : int(c);
+    return HM_OK;
+  } catch (...) {
+    return hm::api_failure();
   }
-  const hm::ClassTables& t = hm::class_tables();
-  if (pattern >= (k == 3 ? 16u : 2048u)) {
-    hm::set_error("pattern %u out of range for order %d", pattern, k);
-    return HM_EINVAL;
-  }
-  uint8_t c = (k == 3) ? t.lut3[pattern] : t.lut4[pattern];
-  *cls = c == 0xFF ? -1 : int(c);
-  return HM_OK;
 }
 
 }  // extern "C"

@@ -450,52 +450,60 @@ int count_exact_impl(const hm_graph* H, int k, int64_t* counts, hipStream_t st) 
 }  // namespace hm
 
 extern "C" int count_exact(const hm_graph* H, int k, int64_t* counts, void* stream) {
-  if (!H || !counts) {
-    hm::set_error("NULL argument to count_exact");
-    return HM_EINVAL;
+  try {
+    if (!H || !counts) {
+      hm::set_error("NULL argument to count_exact");
+      return HM_EINVAL;
+    }
+    if (k != 3 && k != 4) {
+      hm::set_error("order %d is not supported (3 or 4)", k);
+      return HM_EUNSUPPORTED;
+    }
+    return hm::count_exact_impl(H, k, counts, static_cast<hipStream_t>(stream));
+  } catch (...) {
+    return hm::api_failure();
   }
-  if (k != 3 && k != 4) {
-    hm::set_error("order %d is not supported (3 or 4)", k);
-    return HM_EUNSUPPORTED;
-  }
-  return hm::count_exact_impl(H, k, counts, static_cast<hipStream_t>(stream));
 }
 
 extern "C" int count_exact_noalloc(const hm_graph* H, int k, int64_t* counts, void* stream) {
-  if (!H || !counts) {
-    hm::set_error("NULL argument to count_exact_noalloc");
-    return HM_EINVAL;
+  try {
+    if (!H || !counts) {
+      hm::set_error("NULL argument to count_exact_noalloc");
+      return HM_EINVAL;
+    }
+    if (k != 3 && k != 4) {
+      hm::set_error("order %d is not supported (3 or 4)", k);
+      return HM_EUNSUPPORTED;
+    }
+    if (!H->bits) {
+      hm::set_error("count_exact_noalloc counts graphs with adjacency bit rows only (at most %u nodes); this one has "
+                    "%u, and counting it without bit rows needs temporaries sized by the graph",
+                    hm::bitset_max_nodes(), H->n_nodes);
+      return HM_EUNSUPPORTED;
+    }
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev != H->device) {
+      (void)hipGetLastError();
+      hm::set_error("count_exact_noalloc: the graph lives on device %d, the current device is %d", H->device, dev);
+      return HM_EINVAL;
+    }
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    unsigned long long* s = nullptr;
+    HM_TRY(hm::noalloc_scratch(dev, &s));
+    hm::note_use(H, st);
+    const hm::ClassTables& t = hm::class_tables();
+    hm::LutArg luts;
+    std::memcpy(luts.b, t.lut4, 2048);
+    std::memcpy(luts.b + 2048, t.lut3, 16);
+    hm::k_noalloc_prepare<<<16, 256, 0, st>>>(s, luts);
+    HM_HIP(hipGetLastError());
+    const uint8_t* lut = reinterpret_cast<const uint8_t*>(s + hm::kNoAllocHistWords) + (k == 4 ? 0 : 2048);
+    const bool id = hm::launch_bits_count(H, k, lut, s, st);
+    HM_HIP(hipGetLastError());
+    hm::k_combine<<<1, 256, 0, st>>>(s, t.n_classes[k], hm::pairs_only_mask(k), counts, hm::id_shapes(id));
+    HM_HIP(hipGetLastError());
+    return HM_OK;
+  } catch (...) {
+    return hm::api_failure();
   }
-  if (k != 3 && k != 4) {
-    hm::set_error("order %d is not supported (3 or 4)", k);
-    return HM_EUNSUPPORTED;
-  }
-  if (!H->bits) {
-    hm::set_error("count_exact_noalloc counts graphs with adjacency bit rows only (at most %u nodes); this one has "
-                  "%u, and counting it without bit rows needs temporaries sized by the graph",
-                  hm::bitset_max_nodes(), H->n_nodes);
-    return HM_EUNSUPPORTED;
-  }
-  int dev = -1;
-  if (hipGetDevice(&dev) != hipSuccess || dev != H->device) {
-    (void)hipGetLastError();
-    hm::set_error("count_exact_noalloc: the graph lives on device %d, the current device is %d", H->device, dev);
-    return HM_EINVAL;
-  }
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  unsigned long long* s = nullptr;
-  HM_TRY(hm::noalloc_scratch(dev, &s));
-  hm::note_use(H, st);
-  const hm::ClassTables& t = hm::class_tables();
-  hm::LutArg luts;
-  std::memcpy(luts.b, t.lut4, 2048);
-  std::memcpy(luts.b + 2048, t.lut3, 16);
-  hm::k_noalloc_prepare<<<16, 256, 0, st>>>(s, luts);
-  HM_HIP(hipGetLastError());
-  const uint8_t* lut = reinterpret_cast<const uint8_t*>(s + hm::kNoAllocHistWords) + (k == 4 ? 0 : 2048);
-  const bool id = hm::launch_bits_count(H, k, lut, s, st);
-  HM_HIP(hipGetLastError());
-  hm::k_combine<<<1, 256, 0, st>>>(s, t.n_classes[k], hm::pairs_only_mask(k), counts, hm::id_shapes(id));
-  HM_HIP(hipGetLastError());
-  return HM_OK;
 }

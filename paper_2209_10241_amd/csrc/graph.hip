@@ -1380,108 +1380,124 @@ extern "C" {
 
 int hm_graph_create(const uint32_t* members, const uint64_t* offsets, uint64_t n_edges, uint64_t n_members,
                     uint32_t n_nodes, int mem_kind, void* stream, hm_graph** out) {
-  if (!out) {
-    hm::set_error("out is NULL");
-    return HM_EINVAL;
-  }
-  *out = nullptr;
-  if (!offsets || (!members && n_members > 0)) {
-    hm::set_error("members/offsets must not be NULL");
-    return HM_EINVAL;
-  }
-  if (n_nodes == 0 || n_nodes == 0xFFFFFFFFu) {
-    hm::set_error("n_nodes must be in [1, 2^32-2]");
-    return HM_EINVAL;
-  }
-  if (mem_kind != HM_MEM_HOST && mem_kind != HM_MEM_DEVICE) {
-    hm::set_error("mem_kind must be HM_MEM_HOST or HM_MEM_DEVICE");
-    return HM_EINVAL;
-  }
-  if (n_edges >= 0xFFFFFFFFull) {
-    hm::set_error("at most 2^32-2 hyperedges are supported");
-    return HM_EUNSUPPORTED;
-  }
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  hm_graph* H = new (std::nothrow) hm_graph();
-  if (!H) {
-    hm::set_error("host allocation failed");
-    return HM_ENOMEM;
-  }
-  if (hipGetDevice(&H->device) != hipSuccess) {
-    delete H;
-    hm::set_error("no HIP device");
-    return HM_EDEVICE;
-  }
-  H->n_nodes = n_nodes;
-  H->n_input = n_edges;
-  int rc = hm::build(H, members, offsets, n_edges, n_members, mem_kind, st, false);
-  if (rc == hm::kRetryExactDedup) {
-    // two different hyperedges met in the one-launch duplicate search: the
-    // graph is built again with the exact search
-    (void)hipStreamSynchronize(st);
-    hm::release(H);
-    const int device = H->device;
-    *H = hm_graph();
-    H->device = device;
+  try {
+    if (!out) {
+      hm::set_error("out is NULL");
+      return HM_EINVAL;
+    }
+    *out = nullptr;
+    if (!offsets || (!members && n_members > 0)) {
+      hm::set_error("members/offsets must not be NULL");
+      return HM_EINVAL;
+    }
+    if (n_nodes == 0 || n_nodes == 0xFFFFFFFFu) {
+      hm::set_error("n_nodes must be in [1, 2^32-2]");
+      return HM_EINVAL;
+    }
+    if (mem_kind != HM_MEM_HOST && mem_kind != HM_MEM_DEVICE) {
+      hm::set_error("mem_kind must be HM_MEM_HOST or HM_MEM_DEVICE");
+      return HM_EINVAL;
+    }
+    if (n_edges >= 0xFFFFFFFFull) {
+      hm::set_error("at most 2^32-2 hyperedges are supported");
+      return HM_EUNSUPPORTED;
+    }
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    hm_graph* H = new (std::nothrow) hm_graph();
+    if (!H) {
+      hm::set_error("host allocation failed");
+      return HM_ENOMEM;
+    }
+    if (hipGetDevice(&H->device) != hipSuccess) {
+      delete H;
+      hm::set_error("no HIP device");
+      return HM_EDEVICE;
+    }
     H->n_nodes = n_nodes;
     H->n_input = n_edges;
-    rc = hm::build(H, members, offsets, n_edges, n_members, mem_kind, st, true);
+    int rc = hm::build(H, members, offsets, n_edges, n_members, mem_kind, st, false);
+    if (rc == hm::kRetryExactDedup) {
+      // two different hyperedges met in the one-launch duplicate search: the
+      // graph is built again with the exact search
+      (void)hipStreamSynchronize(st);
+      hm::release(H);
+      const int device = H->device;
+      *H = hm_graph();
+      H->device = device;
+      H->n_nodes = n_nodes;
+      H->n_input = n_edges;
+      rc = hm::build(H, members, offsets, n_edges, n_members, mem_kind, st, true);
+    }
+    if (rc != HM_OK) {
+      (void)hipStreamSynchronize(st);
+      hm::release(H);
+      delete H;
+      return rc;
+    }
+    hm::note_use(H, st);
+    *out = H;
+    return HM_OK;
+  } catch (...) {
+    return hm::api_failure();
   }
-  if (rc != HM_OK) {
-    (void)hipStreamSynchronize(st);
-    hm::release(H);
-    delete H;
-    return rc;
-  }
-  hm::note_use(H, st);
-  *out = H;
-  return HM_OK;
 }
 
 int hm_graph_destroy(hm_graph* H) {
-  if (!H) return HM_OK;
-  // a graph used on one stream only, with no captured pipeline or proposal
-  // cache, is released in that stream's order; otherwise after a device-wide
-  // synchronisation
-  if (H->streams.size() == 1 && !H->null_plan && !H->proposal) {
-    hm::release(H, H->streams[0], true);
-  } else {
-    (void)hipDeviceSynchronize();
-    hm::release(H);
+  try {
+    if (!H) return HM_OK;
+    // a graph used on one stream only, with no captured pipeline or proposal
+    // cache, is released in that stream's order; otherwise after a device-wide
+    // synchronisation
+    if (H->streams.size() == 1 && !H->null_plan && !H->proposal) {
+      hm::release(H, H->streams[0], true);
+    } else {
+      (void)hipDeviceSynchronize();
+      hm::release(H);
+    }
+    delete H;
+    return HM_OK;
+  } catch (...) {
+    return hm::api_failure();
   }
-  delete H;
-  return HM_OK;
 }
 
 int hm_graph_stats(const hm_graph* H, uint64_t* out10) {
-  uint64_t* out8 = out10;
-  if (!H || !out8) {
-    hm::set_error("NULL argument");
-    return HM_EINVAL;
+  try {
+    uint64_t* out8 = out10;
+    if (!H || !out8) {
+      hm::set_error("NULL argument");
+      return HM_EINVAL;
+    }
+    out8[0] = H->n_nodes;
+    out8[1] = H->n_by_size[2];
+    out8[2] = H->n_by_size[3];
+    out8[3] = H->n_by_size[4];
+    out8[4] = H->n_by_size[5];
+    out8[5] = H->n_input;
+    out8[6] = H->n_singletons;
+    out8[7] = H->n_duplicates;
+    out8[8] = H->n_unique;
+    out8[9] = H->n_unique_members;
+    return HM_OK;
+  } catch (...) {
+    return hm::api_failure();
   }
-  out8[0] = H->n_nodes;
-  out8[1] = H->n_by_size[2];
-  out8[2] = H->n_by_size[3];
-  out8[3] = H->n_by_size[4];
-  out8[4] = H->n_by_size[5];
-  out8[5] = H->n_input;
-  out8[6] = H->n_singletons;
-  out8[7] = H->n_duplicates;
-  out8[8] = H->n_unique;
-  out8[9] = H->n_unique_members;
-  return HM_OK;
 }
 
 int hm_graph_export(const hm_graph* H, int j, uint32_t* out) {
-  if (!H || !out || j < 2 || j > 4) {
-    hm::set_error("bad arguments to hm_graph_export");
-    return HM_EINVAL;
+  try {
+    if (!H || !out || j < 2 || j > 4) {
+      hm::set_error("bad arguments to hm_graph_export");
+      return HM_EINVAL;
+    }
+    const uint32_t* src = j == 2 ? H->e2 : j == 3 ? H->e3 : H->e4;
+    const uint64_t n = H->n_by_size[j] * uint64_t(j);
+    HM_HIP(hipDeviceSynchronize());   // the build may still be running on its stream
+    if (n) HM_HIP(hipMemcpy(out, src, n * sizeof(uint32_t), hipMemcpyDeviceToHost));
+    return HM_OK;
+  } catch (...) {
+    return hm::api_failure();
   }
-  const uint32_t* src = j == 2 ? H->e2 : j == 3 ? H->e3 : H->e4;
-  const uint64_t n = H->n_by_size[j] * uint64_t(j);
-  HM_HIP(hipDeviceSynchronize());   // the build may still be running on its stream
-  if (n) HM_HIP(hipMemcpy(out, src, n * sizeof(uint32_t), hipMemcpyDeviceToHost));
-  return HM_OK;
 }
 
 }  // extern "C"

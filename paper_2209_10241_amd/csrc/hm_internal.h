@@ -48,6 +48,11 @@ int dedup_tag_bits();
 
 // ----------------------------------------------------------------- errors
 void set_error(const char* fmt, ...);
+// Called from the catch clause that every entry point of the C ABI wraps its
+// body in, so that no exception crosses the ABI: a failed host allocation
+// (std::bad_alloc, what the library's host code can throw) becomes HM_ENOMEM,
+// anything else HM_EINTERNAL, with the message set.
+int api_failure();
 const char* last_error();
 struct Status {
   int code = HM_OK;

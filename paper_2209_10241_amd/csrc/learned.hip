@@ -808,305 +808,349 @@ int build_proposal(const hm_graph* Hc, const hm_model* M, int k, hipStream_t st)
 extern "C" {
 
 int hm_features(const hm_graph* H, int k, float* x, void* stream) {
-  if (!H || !x) {
-    hm::set_error("NULL argument to hm_features");
-    return HM_EINVAL;
+  try {
+    if (!H || !x) {
+      hm::set_error("NULL argument to hm_features");
+      return HM_EINVAL;
+    }
+    if (k != 3 && k != 4) {
+      hm::set_error("order %d is not supported (3 or 4)", k);
+      return HM_EUNSUPPORTED;
+    }
+    hm::Bufs tmp(static_cast<hipStream_t>(stream));
+    return hm::features(H, k, x, tmp, static_cast<hipStream_t>(stream));
+  } catch (...) {
+    return hm::api_failure();
   }
-  if (k != 3 && k != 4) {
-    hm::set_error("order %d is not supported (3 or 4)", k);
-    return HM_EUNSUPPORTED;
-  }
-  hm::Bufs tmp(static_cast<hipStream_t>(stream));
-  return hm::features(H, k, x, tmp, static_cast<hipStream_t>(stream));
 }
 
 int hm_contrib(const hm_graph* H, int k, double* y, void* stream) {
-  if (!H || !y) {
-    hm::set_error("NULL argument to hm_contrib");
-    return HM_EINVAL;
+  try {
+    if (!H || !y) {
+      hm::set_error("NULL argument to hm_contrib");
+      return HM_EINVAL;
+    }
+    if (k != 3 && k != 4) {
+      hm::set_error("order %d is not supported (3 or 4)", k);
+      return HM_EUNSUPPORTED;
+    }
+    return hm::contributions(H, k, y, static_cast<hipStream_t>(stream));
+  } catch (...) {
+    return hm::api_failure();
   }
-  if (k != 3 && k != 4) {
-    hm::set_error("order %d is not supported (3 or 4)", k);
-    return HM_EUNSUPPORTED;
-  }
-  return hm::contributions(H, k, y, static_cast<hipStream_t>(stream));
 }
 
 int hm_mlp_forward(const float* params, const float* x, uint64_t n, float* out, void* stream) {
-  if (!params || (!x && n) || (!out && n)) {
-    hm::set_error("NULL argument to hm_mlp_forward");
-    return HM_EINVAL;
+  try {
+    if (!params || (!x && n) || (!out && n)) {
+      hm::set_error("NULL argument to hm_mlp_forward");
+      return HM_EINVAL;
+    }
+    if (!n) return HM_OK;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    hm::k_mlp_forward<<<hm::mlp_grid(n), hm::kThreads, 0, st>>>(params, x, n, out);
+    HM_HIP(hipGetLastError());
+    return HM_OK;
+  } catch (...) {
+    return hm::api_failure();
   }
-  if (!n) return HM_OK;
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  hm::k_mlp_forward<<<hm::mlp_grid(n), hm::kThreads, 0, st>>>(params, x, n, out);
-  HM_HIP(hipGetLastError());
-  return HM_OK;
 }
 
 int hm_mlp_grad(const float* params, const float* x, const float* t, uint64_t n, float* grad, void* stream) {
-  if (!params || !grad || (n && (!x || !t))) {
-    hm::set_error("NULL argument to hm_mlp_grad");
-    return HM_EINVAL;
+  try {
+    if (!params || !grad || (n && (!x || !t))) {
+      hm::set_error("NULL argument to hm_mlp_grad");
+      return HM_EINVAL;
+    }
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const uint32_t blocks = uint32_t(std::min<uint64_t>((n + 63) / 64 + 1, 256));
+    const uint32_t waves = blocks * hm::kWavesPerBlock;
+    hm::Bufs tmp(st);
+    float* partial = nullptr;
+    HM_TRY(tmp.get(&partial, uint64_t(waves) * (hm::kNParams + 1)));
+    hm::k_mlp_train<<<blocks, hm::kThreads, 0, st>>>(params, x, t, n, n ? 1.f / float(n) : 0.f, partial);
+    hm::k_reduce_partials<<<(hm::kNParams + hm::kReduceParams) / hm::kReduceParams, hm::kThreads, 0, st>>>(partial, waves,
+                                                                                                       grad);
+    HM_HIP(hipGetLastError());
+    HM_HIP(hipStreamSynchronize(st));
+    return HM_OK;
+  } catch (...) {
+    return hm::api_failure();
   }
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  const uint32_t blocks = uint32_t(std::min<uint64_t>((n + 63) / 64 + 1, 256));
-  const uint32_t waves = blocks * hm::kWavesPerBlock;
-  hm::Bufs tmp(st);
-  float* partial = nullptr;
-  HM_TRY(tmp.get(&partial, uint64_t(waves) * (hm::kNParams + 1)));
-  hm::k_mlp_train<<<blocks, hm::kThreads, 0, st>>>(params, x, t, n, n ? 1.f / float(n) : 0.f, partial);
-  hm::k_reduce_partials<<<(hm::kNParams + hm::kReduceParams) / hm::kReduceParams, hm::kThreads, 0, st>>>(partial, waves,
-                                                                                                     grad);
-  HM_HIP(hipGetLastError());
-  HM_HIP(hipStreamSynchronize(st));
-  return HM_OK;
 }
 
 int hm_model_train(const hm_graph* H, int k, const hm_train_opts* opts, hm_model** out) {
-  if (!H || !opts || !out) {
-    hm::set_error("NULL argument to hm_model_train");
-    return HM_EINVAL;
-  }
-  if (k != 3 && k != 4) {
-    hm::set_error("order %d is not supported (3 or 4)", k);
-    return HM_EUNSUPPORTED;
-  }
-  if (opts->epochs < 0 || opts->batch < 16 || !(opts->lr > 0) || !(opts->epsilon > 0 && opts->epsilon <= 1) ||
-      !(opts->gamma >= 0)) {
-    hm::set_error("bad training options");
-    return HM_EINVAL;
-  }
-  *out = nullptr;
-  hipStream_t st = nullptr;
-  hm_model* M = new (std::nothrow) hm_model();
-  if (!M) {
-    hm::set_error("host allocation failed");
-    return HM_ENOMEM;
-  }
-  M->k = k;
-  M->gamma = opts->gamma;
-  M->epsilon = opts->epsilon;
-  M->id = hm::g_model_ids.fetch_add(1);
-  (void)hipGetDevice(&M->device);
-  void* pp = nullptr;
-  int rc = hm::dalloc(&pp, hm::kNParams * sizeof(float));
-  if (rc != HM_OK) {
-    delete M;
-    return rc;
-  }
-  M->params = static_cast<float*>(pp);
-  // initial weights: He for the ReLU layers, biases zero
-  std::vector<float> init(hm::kNParams, 0.f);
-  hm::InitRng rng{opts->seed ^ 0x6a09e667f3bcc908ull};
-  for (int i = 0; i < 1024; ++i) init[hm::kOffW1 + i] = float(rng.normal() * std::sqrt(2.0 / 16.0));
-  for (int i = 0; i < 4096; ++i) init[hm::kOffW2 + i] = float(rng.normal() * std::sqrt(2.0 / 64.0));
-  for (int i = 0; i < 64; ++i) init[hm::kOffW3 + i] = float(rng.normal() * std::sqrt(1.0 / 64.0));
-  rc = hipMemcpy(M->params, init.data(), sizeof(float) * hm::kNParams, hipMemcpyHostToDevice) == hipSuccess
-           ? HM_OK
-           : HM_EDEVICE;
-  uint64_t b[5];
-  const int ns = hm::strata_bounds(H, k, b);
-  const uint64_t n = b[ns];
-  hm::Bufs tmp(st);
-  float *X = nullptr, *t = nullptr, *Xp = nullptr, *tp = nullptr, *stats = nullptr, *partial = nullptr, *grad = nullptr,
-        *m = nullptr, *v = nullptr;
-  double* y = nullptr;
-  uint64_t* db = nullptr;
-  unsigned long long *keys = nullptr, *keys_tmp = nullptr;
-  uint32_t *vals = nullptr, *vals_tmp = nullptr;
-  const uint32_t batch = uint32_t(opts->batch);
-  const uint32_t blocks = std::min<uint32_t>((batch + 63) / 64, 256);
-  const uint32_t waves = blocks * hm::kWavesPerBlock;
-  if (rc == HM_OK) rc = tmp.get(&X, n * hm::kF);
-  if (rc == HM_OK) rc = tmp.get(&t, n);
-  if (rc == HM_OK) rc = tmp.get(&Xp, n * hm::kF);
-  if (rc == HM_OK) rc = tmp.get(&tp, n);
-  if (rc == HM_OK) rc = tmp.get(&y, n);
-  if (rc == HM_OK) rc = tmp.get(&stats, 8);
-  if (rc == HM_OK) rc = tmp.get(&db, 5);
-  if (rc == HM_OK) rc = tmp.get(&partial, uint64_t(waves) * (hm::kNParams + 1));
-  if (rc == HM_OK) rc = tmp.get(&grad, hm::kNParams + 1);
-  if (rc == HM_OK) rc = tmp.get(&m, hm::kNParams);
-  if (rc == HM_OK) rc = tmp.get(&v, hm::kNParams);
-  if (rc == HM_OK) rc = tmp.get(&keys, n);
-  if (rc == HM_OK) rc = tmp.get(&keys_tmp, n);
-  if (rc == HM_OK) rc = tmp.get(&vals, n);
-  if (rc == HM_OK) rc = tmp.get(&vals_tmp, n);
-  // features and exact contributions of the training hypergraph
-  if (rc == HM_OK) rc = hm::features(H, k, X, tmp, st);
-  if (rc == HM_OK) rc = hm::contributions(H, k, y, st);
-  if (rc == HM_OK && n) {
-    hm::k_log1p_targets<<<hm::grid_for(n), 256, 0, st>>>(y, n, t);
-    if (hipMemcpyAsync(db, b, sizeof(uint64_t) * 5, hipMemcpyHostToDevice, st) != hipSuccess) rc = HM_EDEVICE;
-    hm::k_column_stats<<<ns, 256, 0, st>>>(t, 1, db, 1, stats);
-    hm::k_standardise_targets<<<hm::grid_for(n), 256, 0, st>>>(t, db, ns, stats);
-    // one fixed random order of the rows
-    hm::k_perm_keys<<<hm::grid_for(n), 256, 0, st>>>(n, opts->seed, keys, vals);
-    if (hipGetLastError() != hipSuccess) rc = HM_EDEVICE;
-    if (rc == HM_OK) rc = hm::radix_sort_pairs(keys, vals, keys_tmp, vals_tmp, n, 64, st);
-    if (rc == HM_OK) hm::k_gather_rows<<<hm::grid_for(n), 256, 0, st>>>(X, t, vals, n, Xp, tp);
-    if (rc == HM_OK) rc = hm::fill_u32(reinterpret_cast<uint32_t*>(m), 0, hm::kNParams, st);
-    if (rc == HM_OK) rc = hm::fill_u32(reinterpret_cast<uint32_t*>(v), 0, hm::kNParams, st);
-    float host_stats[8] = {0, 1, 0, 1, 0, 1, 0, 1};
-    if (rc == HM_OK && hipMemcpyAsync(host_stats, stats, sizeof(float) * 2 * ns, hipMemcpyDeviceToHost, st) != hipSuccess)
-      rc = HM_EDEVICE;
-    if (rc == HM_OK && hipStreamSynchronize(st) != hipSuccess) rc = HM_EDEVICE;
-    for (int s = 0; s < ns; ++s) M->tstd[s] = host_stats[2 * s + 1] > 0.f ? 1.f / host_stats[2 * s + 1] : 1.f;
-  }
-  // Adam over mini-batches; every step's loss stays on the device and an
-  // epoch's losses are read back once, at its end
-  int step = 0;
-  const float b1 = 0.9f, b2 = 0.999f;
-  const uint64_t batches_per_epoch = n ? (n + batch - 1) / batch : 0;
-  float* losses = nullptr;
-  if (rc == HM_OK) rc = tmp.get(&losses, batches_per_epoch + 1);
-  std::vector<float> host_losses(batches_per_epoch + 1);
-  for (int ep = 0; ep < opts->epochs && rc == HM_OK && n; ++ep) {
-    uint64_t n_batches = 0;
-    for (uint64_t b0 = 0; b0 < n && rc == HM_OK; b0 += batch) {
-      const uint64_t nb = std::min<uint64_t>(batch, n - b0);
-      hm::k_mlp_train<<<blocks, hm::kThreads, 0, st>>>(M->params, Xp + b0 * hm::kF, tp + b0, nb, 1.f / float(nb),
-                                                       partial);
-      hm::k_reduce_partials<<<(hm::kNParams + hm::kReduceParams) / hm::kReduceParams, hm::kThreads, 0, st>>>(
-          partial, waves, grad);
-      ++step;
-      const float c1 = 1.f - std::pow(b1, float(step)), c2 = 1.f - std::pow(b2, float(step));
-      hm::k_adam<<<(hm::kNParams + 255) / 256, 256, 0, st>>>(M->params, grad, m, v, opts->lr, b1, b2, 1e-8f, c1, c2,
-                                                              losses + n_batches);
-      if (hipGetLastError() != hipSuccess) rc = HM_EDEVICE;
-      ++n_batches;
+  try {
+    if (!H || !opts || !out) {
+      hm::set_error("NULL argument to hm_model_train");
+      return HM_EINVAL;
     }
-    if (rc == HM_OK && hipMemcpyAsync(host_losses.data(), losses, sizeof(float) * n_batches, hipMemcpyDeviceToHost,
-                                      st) != hipSuccess)
-      rc = HM_EDEVICE;
-    if (rc == HM_OK && hipStreamSynchronize(st) != hipSuccess) rc = HM_EDEVICE;
-    double ep_loss = 0.0;
-    for (uint64_t i = 0; i < n_batches; ++i) ep_loss += host_losses[i];
-    M->loss.push_back(float(ep_loss / double(std::max<uint64_t>(1, n_batches))));
+    if (k != 3 && k != 4) {
+      hm::set_error("order %d is not supported (3 or 4)", k);
+      return HM_EUNSUPPORTED;
+    }
+    if (opts->epochs < 0 || opts->batch < 16 || !(opts->lr > 0) || !(opts->epsilon > 0 && opts->epsilon <= 1) ||
+        !(opts->gamma >= 0)) {
+      hm::set_error("bad training options");
+      return HM_EINVAL;
+    }
+    *out = nullptr;
+    hipStream_t st = nullptr;
+    hm_model* M = new (std::nothrow) hm_model();
+    if (!M) {
+      hm::set_error("host allocation failed");
+      return HM_ENOMEM;
+    }
+    M->k = k;
+    M->gamma = opts->gamma;
+    M->epsilon = opts->epsilon;
+    M->id = hm::g_model_ids.fetch_add(1);
+    (void)hipGetDevice(&M->device);
+    void* pp = nullptr;
+    int rc = hm::dalloc(&pp, hm::kNParams * sizeof(float));
+    if (rc != HM_OK) {
+      delete M;
+      return rc;
+    }
+    M->params = static_cast<float*>(pp);
+    // initial weights: He for the ReLU layers, biases zero
+    std::vector<float> init(hm::kNParams, 0.f);
+    hm::InitRng rng{opts->seed ^ 0x6a09e667f3bcc908ull};
+    for (int i = 0; i < 1024; ++i) init[hm::kOffW1 + i] = float(rng.normal() * std::sqrt(2.0 / 16.0));
+    for (int i = 0; i < 4096; ++i) init[hm::kOffW2 + i] = float(rng.normal() * std::sqrt(2.0 / 64.0));
+    for (int i = 0; i < 64; ++i) init[hm::kOffW3 + i] = float(rng.normal() * std::sqrt(1.0 / 64.0));
+    rc = hipMemcpy(M->params, init.data(), sizeof(float) * hm::kNParams, hipMemcpyHostToDevice) == hipSuccess
+             ? HM_OK
+             : HM_EDEVICE;
+    uint64_t b[5];
+    const int ns = hm::strata_bounds(H, k, b);
+    const uint64_t n = b[ns];
+    hm::Bufs tmp(st);
+    float *X = nullptr, *t = nullptr, *Xp = nullptr, *tp = nullptr, *stats = nullptr, *partial = nullptr, *grad = nullptr,
+          *m = nullptr, *v = nullptr;
+    double* y = nullptr;
+    uint64_t* db = nullptr;
+    unsigned long long *keys = nullptr, *keys_tmp = nullptr;
+    uint32_t *vals = nullptr, *vals_tmp = nullptr;
+    const uint32_t batch = uint32_t(opts->batch);
+    const uint32_t blocks = std::min<uint32_t>((batch + 63) / 64, 256);
+    const uint32_t waves = blocks * hm::kWavesPerBlock;
+    if (rc == HM_OK) rc = tmp.get(&X, n * hm::kF);
+    if (rc == HM_OK) rc = tmp.get(&t, n);
+    if (rc == HM_OK) rc = tmp.get(&Xp, n * hm::kF);
+    if (rc == HM_OK) rc = tmp.get(&tp, n);
+    if (rc == HM_OK) rc = tmp.get(&y, n);
+    if (rc == HM_OK) rc = tmp.get(&stats, 8);
+    if (rc == HM_OK) rc = tmp.get(&db, 5);
+    if (rc == HM_OK) rc = tmp.get(&partial, uint64_t(waves) * (hm::kNParams + 1));
+    if (rc == HM_OK) rc = tmp.get(&grad, hm::kNParams + 1);
+    if (rc == HM_OK) rc = tmp.get(&m, hm::kNParams);
+    if (rc == HM_OK) rc = tmp.get(&v, hm::kNParams);
+    if (rc == HM_OK) rc = tmp.get(&keys, n);
+    if (rc == HM_OK) rc = tmp.get(&keys_tmp, n);
+    if (rc == HM_OK) rc = tmp.get(&vals, n);
+    if (rc == HM_OK) rc = tmp.get(&vals_tmp, n);
+    // features and exact contributions of the training hypergraph
+    if (rc == HM_OK) rc = hm::features(H, k, X, tmp, st);
+    if (rc == HM_OK) rc = hm::contributions(H, k, y, st);
+    if (rc == HM_OK && n) {
+      hm::k_log1p_targets<<<hm::grid_for(n), 256, 0, st>>>(y, n, t);
+      if (hipMemcpyAsync(db, b, sizeof(uint64_t) * 5, hipMemcpyHostToDevice, st) != hipSuccess) rc = HM_EDEVICE;
+      hm::k_column_stats<<<ns, 256, 0, st>>>(t, 1, db, 1, stats);
+      hm::k_standardise_targets<<<hm::grid_for(n), 256, 0, st>>>(t, db, ns, stats);
+      // one fixed random order of the rows
+      hm::k_perm_keys<<<hm::grid_for(n), 256, 0, st>>>(n, opts->seed, keys, vals);
+      if (hipGetLastError() != hipSuccess) rc = HM_EDEVICE;
+      if (rc == HM_OK) rc = hm::radix_sort_pairs(keys, vals, keys_tmp, vals_tmp, n, 64, st);
+      if (rc == HM_OK) hm::k_gather_rows<<<hm::grid_for(n), 256, 0, st>>>(X, t, vals, n, Xp, tp);
+      if (rc == HM_OK) rc = hm::fill_u32(reinterpret_cast<uint32_t*>(m), 0, hm::kNParams, st);
+      if (rc == HM_OK) rc = hm::fill_u32(reinterpret_cast<uint32_t*>(v), 0, hm::kNParams, st);
+      float host_stats[8] = {0, 1, 0, 1, 0, 1, 0, 1};
+      if (rc == HM_OK && hipMemcpyAsync(host_stats, stats, sizeof(float) * 2 * ns, hipMemcpyDeviceToHost, st) != hipSuccess)
+        rc = HM_EDEVICE;
+      if (rc == HM_OK && hipStreamSynchronize(st) != hipSuccess) rc = HM_EDEVICE;
+      for (int s = 0; s < ns; ++s) M->tstd[s] = host_stats[2 * s + 1] > 0.f ? 1.f / host_stats[2 * s + 1] : 1.f;
+    }
+    // Adam over mini-batches; every step's loss stays on the device and an
+    // epoch's losses are read back once, at its end
+    int step = 0;
+    const float b1 = 0.9f, b2 = 0.999f;
+    const uint64_t batches_per_epoch = n ? (n + batch - 1) / batch : 0;
+    float* losses = nullptr;
+    if (rc == HM_OK) rc = tmp.get(&losses, batches_per_epoch + 1);
+    std::vector<float> host_losses(batches_per_epoch + 1);
+    for (int ep = 0; ep < opts->epochs && rc == HM_OK && n; ++ep) {
+      uint64_t n_batches = 0;
+      for (uint64_t b0 = 0; b0 < n && rc == HM_OK; b0 += batch) {
+        const uint64_t nb = std::min<uint64_t>(batch, n - b0);
+        hm::k_mlp_train<<<blocks, hm::kThreads, 0, st>>>(M->params, Xp + b0 * hm::kF, tp + b0, nb, 1.f / float(nb),
+                                                         partial);
+        hm::k_reduce_partials<<<(hm::kNParams + hm::kReduceParams) / hm::kReduceParams, hm::kThreads, 0, st>>>(
+            partial, waves, grad);
+        ++step;
+        const float c1 = 1.f - std::pow(b1, float(step)), c2 = 1.f - std::pow(b2, float(step));
+        hm::k_adam<<<(hm::kNParams + 255) / 256, 256, 0, st>>>(M->params, grad, m, v, opts->lr, b1, b2, 1e-8f, c1, c2,
+                                                                losses + n_batches);
+        if (hipGetLastError() != hipSuccess) rc = HM_EDEVICE;
+        ++n_batches;
+      }
+      if (rc == HM_OK && hipMemcpyAsync(host_losses.data(), losses, sizeof(float) * n_batches, hipMemcpyDeviceToHost,
+                                        st) != hipSuccess)
+        rc = HM_EDEVICE;
+      if (rc == HM_OK && hipStreamSynchronize(st) != hipSuccess) rc = HM_EDEVICE;
+      double ep_loss = 0.0;
+      for (uint64_t i = 0; i < n_batches; ++i) ep_loss += host_losses[i];
+      M->loss.push_back(float(ep_loss / double(std::max<uint64_t>(1, n_batches))));
+    }
+    if (rc != HM_OK) {
+      hm::dfree(M->params);
+      delete M;
+      return rc;
+    }
+    *out = M;
+    return HM_OK;
+  } catch (...) {
+    return hm::api_failure();
   }
-  if (rc != HM_OK) {
-    hm::dfree(M->params);
-    delete M;
-    return rc;
-  }
-  *out = M;
-  return HM_OK;
 }
 
 int hm_model_destroy(hm_model* M) {
-  if (!M) return HM_OK;
-  (void)hipDeviceSynchronize();
-  hm::dfree(M->params);
-  delete M;
-  return HM_OK;
+  try {
+    if (!M) return HM_OK;
+    (void)hipDeviceSynchronize();
+    hm::dfree(M->params);
+    delete M;
+    return HM_OK;
+  } catch (...) {
+    return hm::api_failure();
+  }
 }
 
 int hm_model_params(const hm_model* M, float* params_out) {
-  if (!M || !params_out) {
-    hm::set_error("NULL argument");
-    return HM_EINVAL;
+  try {
+    if (!M || !params_out) {
+      hm::set_error("NULL argument");
+      return HM_EINVAL;
+    }
+    HM_HIP(hipMemcpy(params_out, M->params, sizeof(float) * hm::kNParams, hipMemcpyDeviceToHost));
+    return HM_OK;
+  } catch (...) {
+    return hm::api_failure();
   }
-  HM_HIP(hipMemcpy(params_out, M->params, sizeof(float) * hm::kNParams, hipMemcpyDeviceToHost));
-  return HM_OK;
 }
 
 int hm_model_loss(const hm_model* M, int max_epochs, float* loss_out) {
-  if (!M) {
-    hm::set_error("NULL argument");
-    return HM_EINVAL;
+  try {
+    if (!M) {
+      hm::set_error("NULL argument");
+      return HM_EINVAL;
+    }
+    const int n = int(M->loss.size());
+    for (int i = 0; i < n && i < max_epochs && loss_out; ++i) loss_out[i] = M->loss[i];
+    return n;
+  } catch (...) {
+    return hm::api_failure();
   }
-  const int n = int(M->loss.size());
-  for (int i = 0; i < n && i < max_epochs && loss_out; ++i) loss_out[i] = M->loss[i];
-  return n;
 }
 
 int hm_proposal_probs(const hm_graph* H, const hm_model* M, int k, double* p, void* stream) {
-  if (!H || !M || !p) {
-    hm::set_error("NULL argument to hm_proposal_probs");
-    return HM_EINVAL;
+  try {
+    if (!H || !M || !p) {
+      hm::set_error("NULL argument to hm_proposal_probs");
+      return HM_EINVAL;
+    }
+    if (k != 3 && k != 4) {
+      hm::set_error("order %d is not supported (3 or 4)", k);
+      return HM_EUNSUPPORTED;
+    }
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    HM_TRY(hm::build_proposal(H, M, k, st));
+    const hm::ProposalCache* C = H->proposal;
+    const uint64_t n = C->bounds[k == 4 ? 3 : 2];
+    if (n) HM_HIP(hipMemcpyAsync(p, C->p, n * sizeof(double), hipMemcpyDeviceToDevice, st));
+    HM_HIP(hipStreamSynchronize(st));
+    return HM_OK;
+  } catch (...) {
+    return hm::api_failure();
   }
-  if (k != 3 && k != 4) {
-    hm::set_error("order %d is not supported (3 or 4)", k);
-    return HM_EUNSUPPORTED;
-  }
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  HM_TRY(hm::build_proposal(H, M, k, st));
-  const hm::ProposalCache* C = H->proposal;
-  const uint64_t n = C->bounds[k == 4 ? 3 : 2];
-  if (n) HM_HIP(hipMemcpyAsync(p, C->p, n * sizeof(double), hipMemcpyDeviceToDevice, st));
-  HM_HIP(hipStreamSynchronize(st));
-  return HM_OK;
 }
 
 int count_sampled_learned(const hm_graph* H, const hm_model* M, int k, double fraction, uint64_t seed, float* est,
                           int64_t* raw, void* stream) {
-  if (!H || !M || !est) {
-    hm::set_error("NULL argument to count_sampled_learned");
-    return HM_EINVAL;
-  }
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  uint64_t S[5];
-  HM_TRY(hm::sample_sizes(H, k, fraction, HM_ALLOC_PROPORTIONAL, S));
-  HM_TRY(hm::build_proposal(H, M, k, st));
-  const hm::ProposalCache* C = H->proposal;
-  hm::Bufs tmp(st);
-  uint64_t total = 0;
-  for (int j = 2; j <= k; ++j) total += S[j];
-  uint32_t* idx = nullptr;
-  double* w = nullptr;
-  HM_TRY(tmp.get(&idx, total + 1));
-  HM_TRY(tmp.get(&w, total + 1));
-  const uint32_t* ix[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
-  uint64_t off = 0;
-  for (int j = 2; j <= k; ++j) {
-    ix[j] = idx + off;
-    const uint64_t lo = C->bounds[j - 2];
-    const uint64_t nj = H->n_by_size[j];
-    if (S[j] && nj) {
-      hm::k_pps_draw<<<hm::grid_for(S[j], 1024), 256, 0, st>>>(C->cdf + lo, C->p + lo, nj, S[j], seed, uint32_t(j),
-                                                              idx + off, w + off);
-      HM_HIP(hipGetLastError());
+  try {
+    if (!H || !M || !est) {
+      hm::set_error("NULL argument to count_sampled_learned");
+      return HM_EINVAL;
     }
-    off += S[j];
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    uint64_t S[5];
+    HM_TRY(hm::sample_sizes(H, k, fraction, HM_ALLOC_PROPORTIONAL, S));
+    HM_TRY(hm::build_proposal(H, M, k, st));
+    const hm::ProposalCache* C = H->proposal;
+    hm::Bufs tmp(st);
+    uint64_t total = 0;
+    for (int j = 2; j <= k; ++j) total += S[j];
+    uint32_t* idx = nullptr;
+    double* w = nullptr;
+    HM_TRY(tmp.get(&idx, total + 1));
+    HM_TRY(tmp.get(&w, total + 1));
+    const uint32_t* ix[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    uint64_t off = 0;
+    for (int j = 2; j <= k; ++j) {
+      ix[j] = idx + off;
+      const uint64_t lo = C->bounds[j - 2];
+      const uint64_t nj = H->n_by_size[j];
+      if (S[j] && nj) {
+        hm::k_pps_draw<<<hm::grid_for(S[j], 1024), 256, 0, st>>>(C->cdf + lo, C->p + lo, nj, S[j], seed, uint32_t(j),
+                                                                idx + off, w + off);
+        HM_HIP(hipGetLastError());
+      }
+      off += S[j];
+    }
+    return hm::hh_from_draws(H, k, ix, S, w, est, raw, st);
+  } catch (...) {
+    return hm::api_failure();
   }
-  return hm::hh_from_draws(H, k, ix, S, w, est, raw, st);
 }
 
 int count_sampled_weighted_indices(const hm_graph* H, int k, const uint32_t* idx2, const double* p2, uint64_t s2,
                                    const uint32_t* idx3, const double* p3, uint64_t s3, const uint32_t* idx4,
                                    const double* p4, uint64_t s4, float* est, int64_t* raw, void* stream) {
-  if (!H || !est) {
-    hm::set_error("NULL argument to count_sampled_weighted_indices");
-    return HM_EINVAL;
-  }
-  if (k != 3 && k != 4) {
-    hm::set_error("order %d is not supported (3 or 4)", k);
-    return HM_EUNSUPPORTED;
-  }
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  const uint32_t* ix[5] = {nullptr, nullptr, idx2, idx3, k == 4 ? idx4 : nullptr};
-  const double* pp[5] = {nullptr, nullptr, p2, p3, k == 4 ? p4 : nullptr};
-  uint64_t S[5] = {0, 0, s2, s3, k == 4 ? s4 : 0};
-  hm::Bufs tmp(st);
-  uint64_t total = S[2] + S[3] + S[4];
-  double* w = nullptr;
-  HM_TRY(tmp.get(&w, total + 1));
-  uint64_t off = 0;
-  for (int j = 2; j <= k; ++j) {
-    if (S[j] && (!ix[j] || !pp[j])) {
-      hm::set_error("index or probability array of stratum %d is NULL", j);
+  try {
+    if (!H || !est) {
+      hm::set_error("NULL argument to count_sampled_weighted_indices");
       return HM_EINVAL;
     }
-    if (S[j]) {
-      hm::k_weights_from_p<<<hm::grid_for(S[j], 1024), 256, 0, st>>>(pp[j], S[j], w + off);
-      HM_HIP(hipGetLastError());
+    if (k != 3 && k != 4) {
+      hm::set_error("order %d is not supported (3 or 4)", k);
+      return HM_EUNSUPPORTED;
     }
-    off += S[j];
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const uint32_t* ix[5] = {nullptr, nullptr, idx2, idx3, k == 4 ? idx4 : nullptr};
+    const double* pp[5] = {nullptr, nullptr, p2, p3, k == 4 ? p4 : nullptr};
+    uint64_t S[5] = {0, 0, s2, s3, k == 4 ? s4 : 0};
+    hm::Bufs tmp(st);
+    uint64_t total = S[2] + S[3] + S[4];
+    double* w = nullptr;
+    HM_TRY(tmp.get(&w, total + 1));
+    uint64_t off = 0;
+    for (int j = 2; j <= k; ++j) {
+      if (S[j] && (!ix[j] || !pp[j])) {
+        hm::set_error("index or probability array of stratum %d is NULL", j);
+        return HM_EINVAL;
+      }
+      if (S[j]) {
+        hm::k_weights_from_p<<<hm::grid_for(S[j], 1024), 256, 0, st>>>(pp[j], S[j], w + off);
+        HM_HIP(hipGetLastError());
+      }
+      off += S[j];
+    }
+    // the index check of count_sampled_indices applies: reuse it through a raw call
+    HM_TRY(count_sampled_indices(H, k, idx2, s2, idx3, s3, idx4, s4, est, raw, stream));
+    return hm::hh_from_draws(H, k, ix, S, w, est, raw, st);
+  } catch (...) {
+    return hm::api_failure();
   }
-  // the index check of count_sampled_indices applies: reuse it through a raw call
-  HM_TRY(count_sampled_indices(H, k, idx2, s2, idx3, s3, idx4, s4, est, raw, stream));
-  return hm::hh_from_draws(H, k, ix, S, w, est, raw, st);
 }
 
 }  // extern "C"

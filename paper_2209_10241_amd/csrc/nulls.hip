@@ -1821,175 +1821,207 @@ static int null_model_args(int model, int sweeps) {
 
 int hm_null_export_model(const hm_graph* H, int model, int sweeps, uint64_t seed, uint32_t copy, uint32_t* members,
                          uint64_t* offsets) {
-  if (!H || !members || !offsets) {
-    hm::set_error("NULL argument to hm_null_export_model");
-    return HM_EINVAL;
+  try {
+    if (!H || !members || !offsets) {
+      hm::set_error("NULL argument to hm_null_export_model");
+      return HM_EINVAL;
+    }
+    HM_TRY(null_model_args(model, sweeps));
+    const uint64_t T = H->n_unique_members;
+    void* buf = nullptr;
+    HM_TRY(hm::dalloc(&buf, T * sizeof(uint32_t) + 4));
+    int rc = hm::null_copies(H, copy, 1, seed, static_cast<uint32_t*>(buf), nullptr, model,
+                             model == HM_NULL_CONFIG ? sweeps : 0);
+    if (rc == HM_OK && T) {
+      if (hipMemcpy(members, buf, T * sizeof(uint32_t), hipMemcpyDeviceToHost) != hipSuccess) rc = HM_EDEVICE;
+    }
+    if (rc == HM_OK &&
+        hipMemcpy(offsets, H->all_off, (H->n_unique + 1) * sizeof(uint64_t), hipMemcpyDeviceToHost) != hipSuccess)
+      rc = HM_EDEVICE;
+    (void)hipDeviceSynchronize();
+    hm::dfree(buf);
+    return rc;
+  } catch (...) {
+    return hm::api_failure();
   }
-  HM_TRY(null_model_args(model, sweeps));
-  const uint64_t T = H->n_unique_members;
-  void* buf = nullptr;
-  HM_TRY(hm::dalloc(&buf, T * sizeof(uint32_t) + 4));
-  int rc = hm::null_copies(H, copy, 1, seed, static_cast<uint32_t*>(buf), nullptr, model,
-                           model == HM_NULL_CONFIG ? sweeps : 0);
-  if (rc == HM_OK && T) {
-    if (hipMemcpy(members, buf, T * sizeof(uint32_t), hipMemcpyDeviceToHost) != hipSuccess) rc = HM_EDEVICE;
-  }
-  if (rc == HM_OK &&
-      hipMemcpy(offsets, H->all_off, (H->n_unique + 1) * sizeof(uint64_t), hipMemcpyDeviceToHost) != hipSuccess)
-    rc = HM_EDEVICE;
-  (void)hipDeviceSynchronize();
-  hm::dfree(buf);
-  return rc;
 }
 
 int hm_null_export(const hm_graph* H, uint64_t seed, uint32_t copy, uint32_t* members, uint64_t* offsets) {
-  return hm_null_export_model(H, HM_NULL_STUBS, 0, seed, copy, members, offsets);
+  try {
+    return hm_null_export_model(H, HM_NULL_STUBS, 0, seed, copy, members, offsets);
+  } catch (...) {
+    return hm::api_failure();
+  }
 }
 
 int count_nulls_model(const hm_graph* H, int k, int n_rand, int model, int sweeps, uint64_t seed, int64_t* real,
                       int64_t* nulls, float* z, void* stream) {
-  if (!H || !nulls) {
-    hm::set_error("NULL argument to count_nulls");
-    return HM_EINVAL;
+  try {
+    if (!H || !nulls) {
+      hm::set_error("NULL argument to count_nulls");
+      return HM_EINVAL;
+    }
+    HM_TRY(null_model_args(model, sweeps));
+    if (k != 3 && k != 4) {
+      hm::set_error("order %d is not supported (3 or 4)", k);
+      return HM_EUNSUPPORTED;
+    }
+    if (n_rand < 2 || n_rand > 65535) {
+      hm::set_error("n_rand must be in [2, 65535]");
+      return HM_EINVAL;
+    }
+    return hm::count_nulls_impl(const_cast<hm_graph*>(H), k, uint32_t(n_rand), model,
+                                model == HM_NULL_CONFIG ? sweeps : 0, seed, real, nulls, z,
+                                static_cast<hipStream_t>(stream));
+  } catch (...) {
+    return hm::api_failure();
   }
-  HM_TRY(null_model_args(model, sweeps));
-  if (k != 3 && k != 4) {
-    hm::set_error("order %d is not supported (3 or 4)", k);
-    return HM_EUNSUPPORTED;
-  }
-  if (n_rand < 2 || n_rand > 65535) {
-    hm::set_error("n_rand must be in [2, 65535]");
-    return HM_EINVAL;
-  }
-  return hm::count_nulls_impl(const_cast<hm_graph*>(H), k, uint32_t(n_rand), model,
-                              model == HM_NULL_CONFIG ? sweeps : 0, seed, real, nulls, z,
-                              static_cast<hipStream_t>(stream));
 }
 
 int count_nulls(const hm_graph* H, int k, int n_rand, uint64_t seed, int64_t* real, int64_t* nulls, float* z,
                 void* stream) {
-  return count_nulls_model(H, k, n_rand, HM_NULL_STUBS, 0, seed, real, nulls, z, stream);
+  try {
+    return count_nulls_model(H, k, n_rand, HM_NULL_STUBS, 0, seed, real, nulls, z, stream);
+  } catch (...) {
+    return hm::api_failure();
+  }
 }
 
 int hm_motif_profile(const double* real, const double* nulls, int n_rand, int n_classes, double eps, double* delta,
                      double* sp, void* stream) {
-  if (!real || !nulls || (!delta && !sp)) {
-    hm::set_error("NULL argument to hm_motif_profile");
-    return HM_EINVAL;
+  try {
+    if (!real || !nulls || (!delta && !sp)) {
+      hm::set_error("NULL argument to hm_motif_profile");
+      return HM_EINVAL;
+    }
+    if (n_rand < 1 || n_classes < 1 || n_classes > 65536 || !(eps >= 0.0)) {
+      hm::set_error("hm_motif_profile needs n_rand >= 1, 1 <= n_classes <= 65536 and eps >= 0");
+      return HM_EINVAL;
+    }
+    hm::k_motif_profile<<<1, 256, 0, static_cast<hipStream_t>(stream)>>>(real, nulls, uint32_t(n_rand), n_classes, eps,
+                                                                         delta, sp);
+    HM_HIP(hipGetLastError());
+    return HM_OK;
+  } catch (...) {
+    return hm::api_failure();
   }
-  if (n_rand < 1 || n_classes < 1 || n_classes > 65536 || !(eps >= 0.0)) {
-    hm::set_error("hm_motif_profile needs n_rand >= 1, 1 <= n_classes <= 65536 and eps >= 0");
-    return HM_EINVAL;
-  }
-  hm::k_motif_profile<<<1, 256, 0, static_cast<hipStream_t>(stream)>>>(real, nulls, uint32_t(n_rand), n_classes, eps,
-                                                                       delta, sp);
-  HM_HIP(hipGetLastError());
-  return HM_OK;
 }
 
 int hm_stratum_search(const hm_graph* H, int k, uint64_t S, const double* ratio3, int n3, const double* ratio4, int n4,
                       int reps, uint64_t seed, const double* nulls, int n_rand, const double* exact_profile, double eps,
                       double* rho, void* stream) {
-  if (!H || !ratio3 || !nulls || !exact_profile || !rho || (k == 4 && !ratio4)) {
-    hm::set_error("NULL argument to hm_stratum_search");
-    return HM_EINVAL;
-  }
-  if (k != 3 && k != 4) {
-    hm::set_error("order %d is not supported (3 or 4)", k);
-    return HM_EUNSUPPORTED;
-  }
-  if (k == 3) n4 = 1;
-  if (S == 0 || S >= (1ull << 31) || n3 < 1 || n4 < 1 || uint64_t(n3) * n4 > 4096 || reps < 1 || reps > 1024 ||
-      n_rand < 1 || !(eps >= 0.0)) {
-    hm::set_error("hm_stratum_search: bad sizes (S, grid, reps or n_rand)");
-    return HM_EINVAL;
-  }
-  for (int i = 0; i < n3; ++i)
-    if (!(ratio3[i] >= 0.0)) {
-      hm::set_error("stratum ratios must be >= 0");
+  try {
+    if (!H || !ratio3 || !nulls || !exact_profile || !rho || (k == 4 && !ratio4)) {
+      hm::set_error("NULL argument to hm_stratum_search");
       return HM_EINVAL;
     }
-  for (int i = 0; k == 4 && i < n4; ++i)
-    if (!(ratio4[i] >= 0.0)) {
-      hm::set_error("stratum ratios must be >= 0");
+    if (k != 3 && k != 4) {
+      hm::set_error("order %d is not supported (3 or 4)", k);
+      return HM_EUNSUPPORTED;
+    }
+    if (k == 3) n4 = 1;
+    if (S == 0 || S >= (1ull << 31) || n3 < 1 || n4 < 1 || uint64_t(n3) * n4 > 4096 || reps < 1 || reps > 1024 ||
+        n_rand < 1 || !(eps >= 0.0)) {
+      hm::set_error("hm_stratum_search: bad sizes (S, grid, reps or n_rand)");
       return HM_EINVAL;
     }
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  const int C = hm::class_tables().n_classes[k];
-  const uint64_t cells = uint64_t(n3) * n4;
-  std::vector<void*> bufs;
-  struct Free {
-    std::vector<void*>& b;
-    hipStream_t st;
-    ~Free() { hm::dfree_on(b.data(), b.size(), st); }
-  } release{bufs, st};
-  auto get = [&](void** p, size_t bytes) {
-    int rc = hm::dalloc(p, bytes);
-    if (rc == HM_OK) bufs.push_back(*p);
-    return rc;
-  };
-  void *est_p = nullptr, *estd_p = nullptr, *delta_p = nullptr, *q_p = nullptr;
-  HM_TRY(get(&est_p, sizeof(float) * C));
-  HM_TRY(get(&estd_p, sizeof(double) * C));
-  HM_TRY(get(&delta_p, sizeof(double) * C));
-  HM_TRY(get(&q_p, sizeof(double) * 3 * cells * reps));
-  float* est = static_cast<float*>(est_p);
-  double* estd = static_cast<double*>(estd_p);
-  double* delta = static_cast<double*>(delta_p);
-  double* q = static_cast<double*>(q_p);
-  for (int i = 0; i < n3; ++i)
-    for (int j = 0; j < n4; ++j) {
-      // S_2 : S_3 : S_4 = 1 : ratio3 : ratio4 with S_2 + S_3 + S_4 = S
-      const double r3 = ratio3[i], r4 = k == 4 ? ratio4[j] : 0.0;
-      uint64_t Sj[5] = {0, 0, 0, 0, 0};
-      Sj[2] = uint64_t(std::llround(double(S) / (1.0 + r3 + r4)));
-      Sj[3] = std::min<uint64_t>(S - Sj[2], uint64_t(std::llround(r3 * double(Sj[2]))));
-      Sj[4] = k == 4 ? S - Sj[2] - Sj[3] : 0;
-      if (k == 3) Sj[3] = S - Sj[2];
-      for (int r = 0; r < reps; ++r) {
-        const uint64_t cell = uint64_t(i) * n4 + j;
-        HM_TRY(hm::sampled_with_sizes(H, k, Sj, seed + uint64_t(r), est, nullptr, st));
-        hm::k_f32_to_f64<<<1, 256, 0, st>>>(est, C, estd);
-        hm::k_motif_profile<<<1, 256, 0, st>>>(estd, nulls, uint32_t(n_rand), C, eps, delta, nullptr);
-        hm::k_profile_quality<<<1, 256, 0, st>>>(delta, exact_profile, C, q + 3 * (cell * reps + r));
-        HM_HIP(hipGetLastError());
+    for (int i = 0; i < n3; ++i)
+      if (!(ratio3[i] >= 0.0)) {
+        hm::set_error("stratum ratios must be >= 0");
+        return HM_EINVAL;
       }
+    for (int i = 0; k == 4 && i < n4; ++i)
+      if (!(ratio4[i] >= 0.0)) {
+        hm::set_error("stratum ratios must be >= 0");
+        return HM_EINVAL;
+      }
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const int C = hm::class_tables().n_classes[k];
+    const uint64_t cells = uint64_t(n3) * n4;
+    std::vector<void*> bufs;
+    struct Free {
+      std::vector<void*>& b;
+      hipStream_t st;
+      ~Free() { hm::dfree_on(b.data(), b.size(), st); }
+    } release{bufs, st};
+    auto get = [&](void** p, size_t bytes) {
+      int rc = hm::dalloc(p, bytes);
+      if (rc == HM_OK) bufs.push_back(*p);
+      return rc;
+    };
+    void *est_p = nullptr, *estd_p = nullptr, *delta_p = nullptr, *q_p = nullptr;
+    HM_TRY(get(&est_p, sizeof(float) * C));
+    HM_TRY(get(&estd_p, sizeof(double) * C));
+    HM_TRY(get(&delta_p, sizeof(double) * C));
+    HM_TRY(get(&q_p, sizeof(double) * 3 * cells * reps));
+    float* est = static_cast<float*>(est_p);
+    double* estd = static_cast<double*>(estd_p);
+    double* delta = static_cast<double*>(delta_p);
+    double* q = static_cast<double*>(q_p);
+    for (int i = 0; i < n3; ++i)
+      for (int j = 0; j < n4; ++j) {
+        // S_2 : S_3 : S_4 = 1 : ratio3 : ratio4 with S_2 + S_3 + S_4 = S
+        const double r3 = ratio3[i], r4 = k == 4 ? ratio4[j] : 0.0;
+        uint64_t Sj[5] = {0, 0, 0, 0, 0};
+        Sj[2] = uint64_t(std::llround(double(S) / (1.0 + r3 + r4)));
+        Sj[3] = std::min<uint64_t>(S - Sj[2], uint64_t(std::llround(r3 * double(Sj[2]))));
+        Sj[4] = k == 4 ? S - Sj[2] - Sj[3] : 0;
+        if (k == 3) Sj[3] = S - Sj[2];
+        for (int r = 0; r < reps; ++r) {
+          const uint64_t cell = uint64_t(i) * n4 + j;
+          HM_TRY(hm::sampled_with_sizes(H, k, Sj, seed + uint64_t(r), est, nullptr, st));
+          hm::k_f32_to_f64<<<1, 256, 0, st>>>(est, C, estd);
+          hm::k_motif_profile<<<1, 256, 0, st>>>(estd, nulls, uint32_t(n_rand), C, eps, delta, nullptr);
+          hm::k_profile_quality<<<1, 256, 0, st>>>(delta, exact_profile, C, q + 3 * (cell * reps + r));
+          HM_HIP(hipGetLastError());
+        }
+      }
+    std::vector<double> host(3 * cells * reps);
+    HM_HIP(hipMemcpyAsync(host.data(), q, sizeof(double) * host.size(), hipMemcpyDeviceToHost, st));
+    HM_HIP(hipStreamSynchronize(st));
+    for (uint64_t c = 0; c < cells; ++c) {
+      double s = 0.0;
+      for (int r = 0; r < reps; ++r) s += host[3 * (c * reps + r)];
+      rho[c] = s / double(reps);
     }
-  std::vector<double> host(3 * cells * reps);
-  HM_HIP(hipMemcpyAsync(host.data(), q, sizeof(double) * host.size(), hipMemcpyDeviceToHost, st));
-  HM_HIP(hipStreamSynchronize(st));
-  for (uint64_t c = 0; c < cells; ++c) {
-    double s = 0.0;
-    for (int r = 0; r < reps; ++r) s += host[3 * (c * reps + r)];
-    rho[c] = s / double(reps);
+    return HM_OK;
+  } catch (...) {
+    return hm::api_failure();
   }
-  return HM_OK;
 }
 
 int hm_profile_quality(const double* est, const double* exact, int n_classes, double* out3, void* stream) {
-  if (!est || !exact || !out3) {
-    hm::set_error("NULL argument to hm_profile_quality");
-    return HM_EINVAL;
+  try {
+    if (!est || !exact || !out3) {
+      hm::set_error("NULL argument to hm_profile_quality");
+      return HM_EINVAL;
+    }
+    if (n_classes < 1 || n_classes > 65536) {
+      hm::set_error("n_classes must be in [1, 65536]");
+      return HM_EINVAL;
+    }
+    hm::k_profile_quality<<<1, 256, 0, static_cast<hipStream_t>(stream)>>>(est, exact, n_classes, out3);
+    HM_HIP(hipGetLastError());
+    return HM_OK;
+  } catch (...) {
+    return hm::api_failure();
   }
-  if (n_classes < 1 || n_classes > 65536) {
-    hm::set_error("n_classes must be in [1, 65536]");
-    return HM_EINVAL;
-  }
-  hm::k_profile_quality<<<1, 256, 0, static_cast<hipStream_t>(stream)>>>(est, exact, n_classes, out3);
-  HM_HIP(hipGetLastError());
-  return HM_OK;
 }
 
 int hm_null_tile_sizes(const hm_graph* H, uint32_t* out3) {
-  if (!H || !out3) {
-    hm::set_error("NULL argument");
-    return HM_EINVAL;
+  try {
+    if (!H || !out3) {
+      hm::set_error("NULL argument");
+      return HM_EINVAL;
+    }
+    if (hm::null_tuned_chunks(H, out3) != HM_OK) {
+      hm::set_error("count_nulls has not run on this graph");
+      return HM_EINVAL;
+    }
+    return HM_OK;
+  } catch (...) {
+    return hm::api_failure();
   }
-  if (hm::null_tuned_chunks(H, out3) != HM_OK) {
-    hm::set_error("count_nulls has not run on this graph");
-    return HM_EINVAL;
-  }
-  return HM_OK;
 }
 
 }  // extern "C"

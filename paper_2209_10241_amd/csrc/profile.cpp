@@ -74,33 +74,45 @@ ProfileScope::~ProfileScope() {
 extern "C" {
 
 int hm_profile_enable(int on) {
-  std::lock_guard<std::mutex> lock(hm::g_mu);
-  hm::g_on = on != 0;
-  return HM_OK;
+  try {
+    std::lock_guard<std::mutex> lock(hm::g_mu);
+    hm::g_on = on != 0;
+    return HM_OK;
+  } catch (...) {
+    return hm::api_failure();
+  }
 }
 
 int hm_profile_reset(void) {
-  std::lock_guard<std::mutex> lock(hm::g_mu);
-  int rc = hm::drain_locked();
-  hm::g_totals.clear();
-  return rc;
+  try {
+    std::lock_guard<std::mutex> lock(hm::g_mu);
+    int rc = hm::drain_locked();
+    hm::g_totals.clear();
+    return rc;
+  } catch (...) {
+    return hm::api_failure();
+  }
 }
 
 int hm_profile_read(int max_entries, char* names, uint64_t* launches, double* total_ms) {
-  std::lock_guard<std::mutex> lock(hm::g_mu);
-  HM_TRY(hm::drain_locked());
-  int n = 0;
-  for (const auto& kv : hm::g_totals) {
-    if (n >= max_entries) break;
-    if (names) {
-      std::strncpy(names + size_t(n) * 64, kv.first.c_str(), 63);
-      names[size_t(n) * 64 + 63] = '\0';
+  try {
+    std::lock_guard<std::mutex> lock(hm::g_mu);
+    HM_TRY(hm::drain_locked());
+    int n = 0;
+    for (const auto& kv : hm::g_totals) {
+      if (n >= max_entries) break;
+      if (names) {
+        std::strncpy(names + size_t(n) * 64, kv.first.c_str(), 63);
+        names[size_t(n) * 64 + 63] = '\0';
+      }
+      if (launches) launches[n] = kv.second.launches;
+      if (total_ms) total_ms[n] = kv.second.ms;
+      ++n;
     }
-    if (launches) launches[n] = kv.second.launches;
-    if (total_ms) total_ms[n] = kv.second.ms;
-    ++n;
+    return n;
+  } catch (...) {
+    return hm::api_failure();
   }
-  return n;
 }
 
 }  // extern "C"

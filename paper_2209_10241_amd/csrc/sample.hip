@@ -1384,126 +1384,150 @@ int sampled_from_indices(const hm_graph* H, int k, const uint32_t* const idx[5],
 extern "C" {
 
 int hm_sample_sizes(const hm_graph* H, int k, double fraction, int allocation, uint64_t* s_out) {
-  if (!H || !s_out) {
-    hm::set_error("NULL argument");
-    return HM_EINVAL;
+  try {
+    if (!H || !s_out) {
+      hm::set_error("NULL argument");
+      return HM_EINVAL;
+    }
+    uint64_t S[5];
+    HM_TRY(hm::sample_sizes(H, k, fraction, allocation, S));
+    s_out[0] = S[2];
+    s_out[1] = S[3];
+    s_out[2] = S[4];
+    return HM_OK;
+  } catch (...) {
+    return hm::api_failure();
   }
-  uint64_t S[5];
-  HM_TRY(hm::sample_sizes(H, k, fraction, allocation, S));
-  s_out[0] = S[2];
-  s_out[1] = S[3];
-  s_out[2] = S[4];
-  return HM_OK;
 }
 
 int hm_sample_sizes_for(int k, const uint64_t* n_by_size, double fraction, int allocation, uint64_t* s_out) {
-  if (!n_by_size || !s_out) {
-    hm::set_error("NULL argument");
-    return HM_EINVAL;
+  try {
+    if (!n_by_size || !s_out) {
+      hm::set_error("NULL argument");
+      return HM_EINVAL;
+    }
+    const uint64_t n[5] = {0, 0, n_by_size[0], n_by_size[1], k == 4 ? n_by_size[2] : 0};
+    uint64_t S[5];
+    HM_TRY(hm::sample_sizes_for(n, k, fraction, allocation, S));
+    s_out[0] = S[2];
+    s_out[1] = S[3];
+    s_out[2] = S[4];
+    return HM_OK;
+  } catch (...) {
+    return hm::api_failure();
   }
-  const uint64_t n[5] = {0, 0, n_by_size[0], n_by_size[1], k == 4 ? n_by_size[2] : 0};
-  uint64_t S[5];
-  HM_TRY(hm::sample_sizes_for(n, k, fraction, allocation, S));
-  s_out[0] = S[2];
-  s_out[1] = S[3];
-  s_out[2] = S[4];
-  return HM_OK;
 }
 
 int hm_sample_draw(const hm_graph* H, int k, double fraction, uint64_t seed, int allocation, uint32_t* idx2,
                    uint32_t* idx3, uint32_t* idx4, void* stream) {
-  if (!H) {
-    hm::set_error("NULL graph");
-    return HM_EINVAL;
-  }
-  uint64_t S[5];
-  HM_TRY(hm::sample_sizes(H, k, fraction, allocation, S));
-  uint32_t* out[5] = {nullptr, nullptr, idx2, idx3, idx4};
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  for (int j = 2; j <= k; ++j) {
-    if (!S[j]) continue;
-    if (!out[j]) {
-      hm::set_error("index buffer for stratum %d is NULL", j);
+  try {
+    if (!H) {
+      hm::set_error("NULL graph");
       return HM_EINVAL;
     }
-    hm::k_draw<<<hm::grid_for(S[j], 256, 1024), 256, 0, st>>>(out[j], S[j], H->n_by_size[j], seed, uint32_t(j));
-    HM_HIP(hipGetLastError());
+    uint64_t S[5];
+    HM_TRY(hm::sample_sizes(H, k, fraction, allocation, S));
+    uint32_t* out[5] = {nullptr, nullptr, idx2, idx3, idx4};
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    for (int j = 2; j <= k; ++j) {
+      if (!S[j]) continue;
+      if (!out[j]) {
+        hm::set_error("index buffer for stratum %d is NULL", j);
+        return HM_EINVAL;
+      }
+      hm::k_draw<<<hm::grid_for(S[j], 256, 1024), 256, 0, st>>>(out[j], S[j], H->n_by_size[j], seed, uint32_t(j));
+      HM_HIP(hipGetLastError());
+    }
+    return HM_OK;
+  } catch (...) {
+    return hm::api_failure();
   }
-  return HM_OK;
 }
 
 int count_sampled(const hm_graph* H, int k, double fraction, uint64_t seed, int allocation, float* est,
                   int64_t* raw, void* stream) {
-  if (!H || !est) {
-    hm::set_error("NULL argument to count_sampled");
-    return HM_EINVAL;
+  try {
+    if (!H || !est) {
+      hm::set_error("NULL argument to count_sampled");
+      return HM_EINVAL;
+    }
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    uint64_t S[5];
+    HM_TRY(hm::sample_sizes(H, k, fraction, allocation, S));
+    const uint32_t* idx[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};   // drawn in the kernel
+    const uint64_t row0[5] = {0, 0, 0, 0, 0};
+    return hm::launch_sampled(H, k, idx, S, seed, nullptr, row0, est, raw, st);
+  } catch (...) {
+    return hm::api_failure();
   }
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  uint64_t S[5];
-  HM_TRY(hm::sample_sizes(H, k, fraction, allocation, S));
-  const uint32_t* idx[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};   // drawn in the kernel
-  const uint64_t row0[5] = {0, 0, 0, 0, 0};
-  return hm::launch_sampled(H, k, idx, S, seed, nullptr, row0, est, raw, st);
 }
 
 int count_sampled_sizes(const hm_graph* H, int k, uint64_t s2, uint64_t s3, uint64_t s4, uint64_t seed, float* est,
                         int64_t* raw, void* stream) {
-  if (!H || !est) {
-    hm::set_error("NULL argument to count_sampled_sizes");
-    return HM_EINVAL;
+  try {
+    if (!H || !est) {
+      hm::set_error("NULL argument to count_sampled_sizes");
+      return HM_EINVAL;
+    }
+    if (k != 3 && k != 4) {
+      hm::set_error("order %d is not supported (3 or 4)", k);
+      return HM_EUNSUPPORTED;
+    }
+    const uint64_t limit = 1ull << 31;
+    if (s2 >= limit || s3 >= limit || s4 >= limit) {
+      hm::set_error("a stratum sample size of 2^31 or more");
+      return HM_EINVAL;
+    }
+    const uint64_t S[5] = {0, 0, s2, s3, k == 4 ? s4 : 0};
+    return hm::sampled_with_sizes(H, k, S, seed, est, raw, static_cast<hipStream_t>(stream));
+  } catch (...) {
+    return hm::api_failure();
   }
-  if (k != 3 && k != 4) {
-    hm::set_error("order %d is not supported (3 or 4)", k);
-    return HM_EUNSUPPORTED;
-  }
-  const uint64_t limit = 1ull << 31;
-  if (s2 >= limit || s3 >= limit || s4 >= limit) {
-    hm::set_error("a stratum sample size of 2^31 or more");
-    return HM_EINVAL;
-  }
-  const uint64_t S[5] = {0, 0, s2, s3, k == 4 ? s4 : 0};
-  return hm::sampled_with_sizes(H, k, S, seed, est, raw, static_cast<hipStream_t>(stream));
 }
 
 int count_sampled_indices(const hm_graph* H, int k, const uint32_t* idx2, uint64_t s2, const uint32_t* idx3,
                           uint64_t s3, const uint32_t* idx4, uint64_t s4, float* est, int64_t* raw, void* stream) {
-  if (!H || !est) {
-    hm::set_error("NULL argument to count_sampled_indices");
-    return HM_EINVAL;
-  }
-  if (k != 3 && k != 4) {
-    hm::set_error("order %d is not supported (3 or 4)", k);
-    return HM_EUNSUPPORTED;
-  }
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  const uint32_t* idx[5] = {nullptr, nullptr, idx2, idx3, k == 4 ? idx4 : nullptr};
-  uint64_t S[5] = {0, 0, s2, s3, k == 4 ? s4 : 0};
-  // every index must lie in its stratum
-  void* bad_p = nullptr;
-  HM_TRY(hm::dalloc(&bad_p, sizeof(uint32_t)));
-  uint32_t* bad = static_cast<uint32_t*>(bad_p);
-  int rc = hm::fill_u32(bad, 0, 1, st);
-  for (int j = 2; j <= k && rc == HM_OK; ++j) {
-    if (!S[j]) continue;
-    if (!idx[j]) {
-      hm::set_error("index array for stratum %d is NULL", j);
-      rc = HM_EINVAL;
-      break;
+  try {
+    if (!H || !est) {
+      hm::set_error("NULL argument to count_sampled_indices");
+      return HM_EINVAL;
     }
-    hm::k_check_indices<<<hm::grid_for(S[j], 256, 1024), 256, 0, st>>>(idx[j], S[j], H->n_by_size[j], bad);
-    if (hipGetLastError() != hipSuccess) rc = HM_EDEVICE;
+    if (k != 3 && k != 4) {
+      hm::set_error("order %d is not supported (3 or 4)", k);
+      return HM_EUNSUPPORTED;
+    }
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const uint32_t* idx[5] = {nullptr, nullptr, idx2, idx3, k == 4 ? idx4 : nullptr};
+    uint64_t S[5] = {0, 0, s2, s3, k == 4 ? s4 : 0};
+    // every index must lie in its stratum
+    void* bad_p = nullptr;
+    HM_TRY(hm::dalloc(&bad_p, sizeof(uint32_t)));
+    uint32_t* bad = static_cast<uint32_t*>(bad_p);
+    int rc = hm::fill_u32(bad, 0, 1, st);
+    for (int j = 2; j <= k && rc == HM_OK; ++j) {
+      if (!S[j]) continue;
+      if (!idx[j]) {
+        hm::set_error("index array for stratum %d is NULL", j);
+        rc = HM_EINVAL;
+        break;
+      }
+      hm::k_check_indices<<<hm::grid_for(S[j], 256, 1024), 256, 0, st>>>(idx[j], S[j], H->n_by_size[j], bad);
+      if (hipGetLastError() != hipSuccess) rc = HM_EDEVICE;
+    }
+    uint32_t host_bad = 0;
+    if (rc == HM_OK && (hipMemcpyAsync(&host_bad, bad, sizeof(uint32_t), hipMemcpyDeviceToHost, st) != hipSuccess ||
+                        hipStreamSynchronize(st) != hipSuccess))
+      rc = HM_EDEVICE;
+    hm::dfree(bad_p);
+    if (rc != HM_OK) return rc;
+    if (host_bad) {
+      hm::set_error("a sample index lies outside its stratum");
+      return HM_EINVAL;
+    }
+    return hm::sampled_from_indices(H, k, idx, S, est, raw, st);
+  } catch (...) {
+    return hm::api_failure();
   }
-  uint32_t host_bad = 0;
-  if (rc == HM_OK && (hipMemcpyAsync(&host_bad, bad, sizeof(uint32_t), hipMemcpyDeviceToHost, st) != hipSuccess ||
-                      hipStreamSynchronize(st) != hipSuccess))
-    rc = HM_EDEVICE;
-  hm::dfree(bad_p);
-  if (rc != HM_OK) return rc;
-  if (host_bad) {
-    hm::set_error("a sample index lies outside its stratum");
-    return HM_EINVAL;
-  }
-  return hm::sampled_from_indices(H, k, idx, S, est, raw, st);
 }
 
 }  // extern "C"

@@ -711,66 +711,78 @@ int sampled5(hm_graph* H, const uint32_t* const idx[6], const uint64_t S[6], uin
 extern "C" {
 
 int hm_order5_sizes(const hm_graph* H, uint64_t* n_by_size4, void* stream) {
-  if (!H || !n_by_size4) {
-    hm::set_error("NULL argument to hm_order5_sizes");
-    return HM_EINVAL;
+  try {
+    if (!H || !n_by_size4) {
+      hm::set_error("NULL argument to hm_order5_sizes");
+      return HM_EINVAL;
+    }
+    HM_TRY(hm::ensure_order5(const_cast<hm_graph*>(H), static_cast<hipStream_t>(stream)));
+    n_by_size4[0] = H->n_by_size[2];
+    n_by_size4[1] = H->n_by_size[3];
+    n_by_size4[2] = H->n_by_size[4];
+    n_by_size4[3] = H->n5;
+    return HM_OK;
+  } catch (...) {
+    return hm::api_failure();
   }
-  HM_TRY(hm::ensure_order5(const_cast<hm_graph*>(H), static_cast<hipStream_t>(stream)));
-  n_by_size4[0] = H->n_by_size[2];
-  n_by_size4[1] = H->n_by_size[3];
-  n_by_size4[2] = H->n_by_size[4];
-  n_by_size4[3] = H->n5;
-  return HM_OK;
 }
 
 int count_sampled5(const hm_graph* H, double fraction, uint64_t seed, uint64_t capacity, uint32_t* canon, int64_t* raw,
                    float* est, uint64_t* n_classes, void* stream) {
-  if (!H || !canon || !raw || !est || !n_classes) {
-    hm::set_error("NULL argument to count_sampled5");
-    return HM_EINVAL;
+  try {
+    if (!H || !canon || !raw || !est || !n_classes) {
+      hm::set_error("NULL argument to count_sampled5");
+      return HM_EINVAL;
+    }
+    if (!(fraction > 0.0 && fraction <= 1.0)) {
+      hm::set_error("fraction must be in (0, 1]");
+      return HM_EINVAL;
+    }
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    HM_TRY(hm::ensure_order5(const_cast<hm_graph*>(H), st));
+    const uint64_t nj[6] = {0, 0, H->n_by_size[2], H->n_by_size[3], H->n_by_size[4], H->n5};
+    uint64_t S[6] = {0, 0, 0, 0, 0, 0};
+    for (int j = 2; j <= 5; ++j) S[j] = uint64_t(std::ceil(fraction * double(nj[j])));
+    const uint32_t* idx[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    return hm::sampled5(const_cast<hm_graph*>(H), idx, S, seed, capacity, canon, raw, est, n_classes, st);
+  } catch (...) {
+    return hm::api_failure();
   }
-  if (!(fraction > 0.0 && fraction <= 1.0)) {
-    hm::set_error("fraction must be in (0, 1]");
-    return HM_EINVAL;
-  }
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  HM_TRY(hm::ensure_order5(const_cast<hm_graph*>(H), st));
-  const uint64_t nj[6] = {0, 0, H->n_by_size[2], H->n_by_size[3], H->n_by_size[4], H->n5};
-  uint64_t S[6] = {0, 0, 0, 0, 0, 0};
-  for (int j = 2; j <= 5; ++j) S[j] = uint64_t(std::ceil(fraction * double(nj[j])));
-  const uint32_t* idx[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
-  return hm::sampled5(const_cast<hm_graph*>(H), idx, S, seed, capacity, canon, raw, est, n_classes, st);
 }
 
 int count_sampled5_indices(const hm_graph* H, const uint32_t* idx2, uint64_t s2, const uint32_t* idx3, uint64_t s3,
                            const uint32_t* idx4, uint64_t s4, const uint32_t* idx5, uint64_t s5, uint64_t capacity,
                            uint32_t* canon, int64_t* raw, float* est, uint64_t* n_classes, void* stream) {
-  if (!H || !canon || !raw || !est || !n_classes) {
-    hm::set_error("NULL argument to count_sampled5_indices");
-    return HM_EINVAL;
-  }
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  HM_TRY(hm::ensure_order5(const_cast<hm_graph*>(H), st));
-  const uint32_t* idx[6] = {nullptr, nullptr, idx2, idx3, idx4, idx5};
-  const uint64_t S[6] = {0, 0, s2, s3, s4, s5};
-  const uint64_t nj[6] = {0, 0, H->n_by_size[2], H->n_by_size[3], H->n_by_size[4], H->n5};
-  for (int j = 2; j <= 5; ++j)
-    if (S[j] && (!idx[j] || !nj[j])) {
-      hm::set_error("stratum %d: draws without an index array or from an empty stratum", j);
+  try {
+    if (!H || !canon || !raw || !est || !n_classes) {
+      hm::set_error("NULL argument to count_sampled5_indices");
       return HM_EINVAL;
     }
-  // every index must lie in its stratum (checked on the host copy)
-  for (int j = 2; j <= 5; ++j) {
-    if (!S[j]) continue;
-    std::vector<uint32_t> h(S[j]);
-    HM_HIP(hipMemcpy(h.data(), idx[j], S[j] * 4, hipMemcpyDeviceToHost));
-    for (uint32_t x : h)
-      if (x >= nj[j]) {
-        hm::set_error("a sample index lies outside its stratum");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    HM_TRY(hm::ensure_order5(const_cast<hm_graph*>(H), st));
+    const uint32_t* idx[6] = {nullptr, nullptr, idx2, idx3, idx4, idx5};
+    const uint64_t S[6] = {0, 0, s2, s3, s4, s5};
+    const uint64_t nj[6] = {0, 0, H->n_by_size[2], H->n_by_size[3], H->n_by_size[4], H->n5};
+    for (int j = 2; j <= 5; ++j)
+      if (S[j] && (!idx[j] || !nj[j])) {
+        hm::set_error("stratum %d: draws without an index array or from an empty stratum", j);
         return HM_EINVAL;
       }
+    // every index must lie in its stratum (checked on the host copy)
+    for (int j = 2; j <= 5; ++j) {
+      if (!S[j]) continue;
+      std::vector<uint32_t> h(S[j]);
+      HM_HIP(hipMemcpy(h.data(), idx[j], S[j] * 4, hipMemcpyDeviceToHost));
+      for (uint32_t x : h)
+        if (x >= nj[j]) {
+          hm::set_error("a sample index lies outside its stratum");
+          return HM_EINVAL;
+        }
+    }
+    return hm::sampled5(const_cast<hm_graph*>(H), idx, S, 0, capacity, canon, raw, est, n_classes, st);
+  } catch (...) {
+    return hm::api_failure();
   }
-  return hm::sampled5(const_cast<hm_graph*>(H), idx, S, 0, capacity, canon, raw, est, n_classes, st);
 }
 
 }  // extern "C"
